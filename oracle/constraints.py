@@ -1,0 +1,79 @@
+"""Constraints Phi(gamma) = 0 and their exact Jacobians, in float64 (oracle).
+
+Test infrastructure only (see the package docstring).
+
+Definitions (paper Sec. 7.1 "Constraints and Potentials"):
+
+* Barycenter: ``Phi_b = sum_I l_I (x_I - x_0)`` (3 rows, unnormalised as
+  printed).  Its Jacobian block at vertex v is
+  ``sum_{I incident to v} [ (l_I / 2) Id_3 +- (x_I - x_0) T_I^T ]`` with ``+``
+  when v is the edge's second endpoint and ``-`` when it is the first, since
+  ``dl_I/dg_i2 = T_I = -dl_I/dg_i1`` and ``dx_I/dg_ia = Id_3 / 2``.
+* Total length: ``Phi_L = L0 - sum_I l_I`` (1 row).
+* Edge length: ``Phi_I = l0_I - l_I`` (one row per edge) with Jacobian
+  ``+T_I`` at i1 and ``-T_I`` at i2.
+
+Rows are stacked in the order barycenter, total length, edge lengths.
+Vectors in R^{3|V|} are vertex-major: entry ``3 v + c`` is coordinate c of
+vertex v.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .tpe import edge_geometry
+
+__all__ = ["BARYCENTER", "TOTAL_LENGTH", "EDGE_LENGTH", "reference_values", "evaluate"]
+
+BARYCENTER = 1
+TOTAL_LENGTH = 2
+EDGE_LENGTH = 4
+
+
+def reference_values(gamma, edges):
+    """(x0, L0, l0) of a curve: the targets that make Phi(gamma) = 0.
+
+    ``x0`` is the length-weighted barycenter ``sum l_I x_I / sum l_I``.
+    """
+    ell, _, x = edge_geometry(gamma, edges)
+    return (ell[:, None] * x).sum(0) / ell.sum(), float(ell.sum()), ell.copy()
+
+
+def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True):
+    """(Phi, C) for the constraint set ``mask`` (bitwise OR of the flags)."""
+    g = np.asarray(gamma, dtype=np.float64)
+    e = np.asarray(edges)
+    nV, nE = len(g), len(e)
+    ell, T, x = edge_geometry(g, e)
+    phis, jacs = [], []
+    if mask & BARYCENTER:
+        phis.append((ell[:, None] * (x - x0)).sum(0))
+        if jacobian:
+            Cb = np.zeros((3, 3 * nV))
+            for I in range(nE):
+                for a, sgn in ((0, -1.0), (1, 1.0)):
+                    v = e[I, a]
+                    Cb[:, 3 * v:3 * v + 3] += 0.5 * ell[I] * np.eye(3) + sgn * np.outer(x[I] - x0, T[I])
+            jacs.append(Cb)
+    if mask & TOTAL_LENGTH:
+        phis.append(np.array([L0 - ell.sum()]))
+        if jacobian:
+            Cl = np.zeros((1, 3 * nV))
+            for I in range(nE):
+                Cl[0, 3 * e[I, 0]:3 * e[I, 0] + 3] += T[I]
+                Cl[0, 3 * e[I, 1]:3 * e[I, 1] + 3] -= T[I]
+            jacs.append(Cl)
+    if mask & EDGE_LENGTH:
+        phis.append(l0 - ell)
+        if jacobian:
+            Ce = np.zeros((nE, 3 * nV))
+            for I in range(nE):
+                Ce[I, 3 * e[I, 0]:3 * e[I, 0] + 3] = T[I]
+                Ce[I, 3 * e[I, 1]:3 * e[I, 1] + 3] = -T[I]
+            jacs.append(Ce)
+    phi = np.concatenate(phis) if phis else np.zeros(0)
+    if not jacobian:
+        return phi, None
+    C = np.concatenate(jacs) if jacs else np.zeros((0, 3 * nV))
+    return phi, C

@@ -1,0 +1,150 @@
+"""Projected Sobolev gradient, constraint projection and the step, in float64 (oracle).
+
+Test infrastructure only (see the package docstring).
+
+Definitions (paper Sec. 4.3-4.4 and App. B.3.3-B.3.4):
+
+* Eq. GradientSaddlePointProblem: ``[[Abar, C^T], [C, 0]] [g; lam] = [dE; 0]``
+  with ``Abar`` the componentwise operator (eq. VectorInnerProduct).  In the
+  vertex-major ordering used here ``Abar = kron(A, Id_3)``.
+* Eq. ConstraintSaddlePointProblem: one projection iteration solves
+  ``[[Abar, C^T], [C, 0]] [x; mu] = [0; -Phi(gamma~)]`` and sets
+  ``gamma~ += x``; ``Abar`` and ``C`` stay those of the curve before the step
+  (the factorisation of the gradient system is reused).
+* App. B.3.4, eq. SaddleSolutionTransformation: the same x is
+  ``x = z - y`` with ``z = C^T (C C^T)^-1 b`` and y the solution of the
+  gradient-type system with right-hand side ``Abar z``.  Here the pseudoinverse
+  is read as ``C^T (C C^T)^-1`` (the product printed in App. B.3.3 does not
+  type-check as written).
+* Sec. 4.4: normalise the projected gradient by its Euclidean norm, start at
+  ``tau = 1`` and halve tau until the constraint projection succeeds and the
+  Armijo condition ``E(gamma_new) <= E(gamma) - c tau <dE, g_hat>`` holds
+  (backtracking in the sense of the cited textbook algorithm; constants
+  ``c = 0.01`` and factor 1/2).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import constraints as cons
+from . import sobolev, tpe
+
+__all__ = [
+    "saddle_matrix",
+    "projected_gradient",
+    "projected_gradient_schur",
+    "projection_increment",
+    "projection_increment_transform",
+    "project",
+    "line_search",
+    "step",
+]
+
+
+def saddle_matrix(A, C):
+    Abar = np.kron(A, np.eye(3))
+    k = C.shape[0]
+    return np.block([[Abar, C.T], [C, np.zeros((k, k))]])
+
+
+def projected_gradient(A, C, dE):
+    """(g_tilde [V,3], lam) from the full saddle system (eq. GradientSaddlePointProblem)."""
+    n = 3 * A.shape[0]
+    rhs = np.concatenate([np.asarray(dE).ravel(), np.zeros(C.shape[0])])
+    sol = sla.solve(saddle_matrix(A, C), rhs, assume_a="sym")
+    return sol[:n].reshape(-1, 3), sol[n:]
+
+
+def projected_gradient_schur(A, C, dE):
+    """Same solution by a different route: augmented SPD block plus Schur complement.
+
+    Because C g = 0, adding ``C^T C`` to ``Abar`` leaves the solution unchanged
+    and makes the block positive definite (Abar is definite on null(C)).
+    """
+    Abar = np.kron(A, np.eye(3))
+    H = Abar + C.T @ C
+    cf = sla.cho_factor(H)
+    b = np.asarray(dE).ravel()
+    HinvCt = sla.cho_solve(cf, C.T)
+    S = C @ HinvCt
+    lam = np.linalg.solve(S, C @ sla.cho_solve(cf, b))
+    g = sla.cho_solve(cf, b - C.T @ lam)
+    return g.reshape(-1, 3), lam
+
+
+def projection_increment(A, C, phi):
+    """x solving [[Abar, C^T], [C, 0]] [x; mu] = [0; -phi] (eq. ConstraintSaddlePointProblem)."""
+    n = 3 * A.shape[0]
+    rhs = np.concatenate([np.zeros(n), -np.asarray(phi)])
+    sol = sla.solve(saddle_matrix(A, C), rhs, assume_a="sym")
+    return sol[:n].reshape(-1, 3)
+
+
+def projection_increment_transform(A, C, phi):
+    """Same x through eq. SaddleSolutionTransformation: x = z - y."""
+    b = -np.asarray(phi)
+    z = C.T @ np.linalg.solve(C @ C.T, b)
+    Abar = np.kron(A, np.eye(3))
+    y, _ = projected_gradient(A, C, Abar @ z)
+    return (z - y.ravel()).reshape(-1, 3)
+
+
+def _phi_tolerance(gamma, edges, mask):
+    """Per-row projection tolerance: 1e-10 l_mean (lengths), 1e-10 L l_mean (barycenter)."""
+    ell, _, _ = tpe.edge_geometry(gamma, edges)
+    lbar, L = ell.mean(), ell.sum()
+    tol = []
+    if mask & cons.BARYCENTER:
+        tol += [1e-10 * L * lbar] * 3
+    if mask & cons.TOTAL_LENGTH:
+        tol += [1e-10 * L]
+    if mask & cons.EDGE_LENGTH:
+        tol += [1e-10 * lbar] * len(edges)
+    return np.array(tol)
+
+
+def project(gamma_t, edges, A, C, mask, refs, max_iter=10, tol=None):
+    """Iterate the projection increment from gamma_t; returns (gamma, iters, ok)."""
+    x0, L0, l0 = refs
+    g = np.array(gamma_t, dtype=np.float64)
+    tol = _phi_tolerance(g, edges, mask) if tol is None else tol
+    for it in range(max_iter + 1):
+        phi, _ = cons.evaluate(g, edges, mask, x0, L0, l0, jacobian=False)
+        if np.all(np.abs(phi) <= tol):
+            return g, it, True
+        if it == max_iter:
+            break
+        g = g + projection_increment(A, C, phi)
+    return g, max_iter, False
+
+
+def line_search(gamma, edges, alpha, beta, E0, dE, g_tilde, A, C, mask, refs,
+                c_armijo=0.01, shrink=0.5, max_backtracks=30, tau0=1.0):
+    """Backtracking step of Sec. 4.4; returns (gamma_new, tau, E_new, info)."""
+    ghat = g_tilde / np.linalg.norm(g_tilde)
+    slope = float(np.sum(dE * ghat))
+    tau = tau0
+    for bt in range(max_backtracks + 1):
+        cand = gamma - tau * ghat
+        proj, iters, ok = project(cand, edges, A, C, mask, refs)
+        if ok:
+            E1 = tpe.energy(proj, edges, alpha, beta)
+            if E1 <= E0 - c_armijo * tau * slope:
+                return proj, tau, E1, dict(backtracks=bt, proj_iters=iters, ok=True)
+        tau *= shrink
+    return gamma, 0.0, E0, dict(backtracks=max_backtracks, proj_iters=0, ok=False)
+
+
+def step(gamma, edges, alpha, beta, mask, refs):
+    """One projected Sobolev step: dE, A, C, g_tilde, line search."""
+    E0, dE = tpe.differential(gamma, edges, alpha, beta)
+    B, B0 = sobolev.assemble(gamma, edges, alpha, beta)
+    A = B + B0
+    x0, L0, l0 = refs
+    _, C = cons.evaluate(gamma, edges, mask, x0, L0, l0)
+    g, _ = projected_gradient(A, C, dE)
+    new, tau, E1, info = line_search(gamma, edges, alpha, beta, E0, dE, g, A, C, mask, refs)
+    info.update(E0=E0, E1=E1, tau=tau, g=g, dE=dE)
+    return new, info

@@ -1,0 +1,95 @@
+"""Pins of the oracle's constraints, saddle solves and step (Sec. 4.3-4.4, 7.1, App. B.3).
+
+* The constraint Jacobians equal central differences of Phi.
+* The full saddle solve and an independent route (augmented SPD block plus
+  Schur complement) agree; the KKT conditions of eq.
+  GradientSaddlePointProblem hold.
+* Variational identity g^T Abar d = dE . d for every d in null(C), and the
+  descent identity dE . g = g^T Abar g > 0.
+* Scaling: g(lambda gamma) = lambda^(alpha - beta + 2 (beta - 1)/alpha) g(gamma).
+* The projection increment of eq. ConstraintSaddlePointProblem equals the
+  transformed solve of eq. SaddleSolutionTransformation.
+* A step restores the constraints, satisfies the Armijo condition and lowers
+  the energy.
+"""
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import gen
+from oracle import constraints as cons
+from oracle import solve, sobolev, tpe
+
+MASKS = [cons.BARYCENTER, cons.BARYCENTER | cons.EDGE_LENGTH, cons.BARYCENTER | cons.TOTAL_LENGTH]
+
+
+def setup(n=40, seed=21, alpha=2.0, beta=4.5, mask=cons.BARYCENTER, scale=1.0):
+    g, e = gen.trefoil(n, seed=seed)
+    g = g * scale
+    refs = cons.reference_values(g, e)
+    E, dE = tpe.differential(g, e, alpha, beta)
+    A = sum(sobolev.assemble(g, e, alpha, beta))
+    phi, C = cons.evaluate(g, e, mask, *refs)
+    return g, e, refs, E, dE, A, phi, C
+
+
+@pytest.mark.parametrize("mask", MASKS)
+def test_jacobian_matches_central_differences(mask):
+    g, e, refs, *_ , C = setup(mask=mask)
+    h = 1e-6
+    for v, c in [(0, 0), (7, 2), (39, 1)]:
+        gp, gm = g.copy(), g.copy()
+        gp[v, c] += h
+        gm[v, c] -= h
+        fd = (cons.evaluate(gp, e, mask, *refs, jacobian=False)[0]
+              - cons.evaluate(gm, e, mask, *refs, jacobian=False)[0]) / (2 * h)
+        assert np.allclose(C[:, 3 * v + c], fd, rtol=1e-7, atol=1e-8)
+
+
+@pytest.mark.parametrize("mask", MASKS)
+def test_saddle_two_routes_and_kkt(mask):
+    g, e, refs, E, dE, A, phi, C = setup(mask=mask)
+    assert np.abs(phi).max() < 1e-12
+    gt, lam = solve.projected_gradient(A, C, dE)
+    gs, lams = solve.projected_gradient_schur(A, C, dE)
+    assert np.abs(gt - gs).max() < 1e-10 * np.abs(gt).max()
+    assert np.abs(lam - lams).max() < 1e-8 * (np.abs(lam).max() + 1)
+    Abar = np.kron(A, np.eye(3))
+    assert np.abs(C @ gt.ravel()).max() < 1e-10 * np.abs(gt).max()
+    kkt = Abar @ gt.ravel() + C.T @ lam - dE.ravel()
+    assert np.abs(kkt).max() < 1e-9 * np.abs(dE).max()
+    # variational identity on null(C) and the descent identity
+    N = sla.null_space(C)
+    d = N @ np.random.default_rng(0).normal(size=N.shape[1])
+    assert gt.ravel() @ Abar @ d == pytest.approx(dE.ravel() @ d, rel=1e-8)
+    q = gt.ravel() @ Abar @ gt.ravel()
+    assert q > 0 and np.sum(dE * gt) == pytest.approx(q, rel=1e-9)
+
+
+@pytest.mark.parametrize("alpha,beta", [(2.0, 4.0), (2.0, 4.5), (3.0, 6.0)])
+def test_gradient_scaling(alpha, beta):
+    lam = 1.6
+    g1 = solve.projected_gradient(*[setup(alpha=alpha, beta=beta)[i] for i in (5, 7, 4)])[0]
+    g2 = solve.projected_gradient(*[setup(alpha=alpha, beta=beta, scale=lam)[i] for i in (5, 7, 4)])[0]
+    expo = alpha - beta + 2 * (beta - 1) / alpha
+    assert np.allclose(g2, lam ** expo * g1, rtol=1e-8, atol=1e-10 * np.abs(g2).max())
+
+
+@pytest.mark.parametrize("mask", MASKS)
+def test_projection_transform_and_step(mask):
+    g, e, refs, E, dE, A, phi, C = setup(mask=mask)
+    target = phi + np.random.default_rng(1).normal(size=phi.shape) * 1e-3
+    x1 = solve.projection_increment(A, C, target)
+    x2 = solve.projection_increment_transform(A, C, target)
+    assert np.abs(x1 - x2).max() < 1e-10 * np.abs(x1).max()
+    assert np.allclose(C @ x1.ravel(), -target, atol=1e-12)
+    new, info = solve.step(g, e, 2.0, 4.5, mask, refs)
+    assert info["ok"] and info["tau"] > 0
+    ghat = info["g"] / np.linalg.norm(info["g"])
+    assert info["E1"] <= info["E0"] - 0.01 * info["tau"] * np.sum(info["dE"] * ghat)
+    assert info["E1"] < info["E0"]
+    phi_new, _ = cons.evaluate(new, e, mask, *refs, jacobian=False)
+    ell, _, _ = tpe.edge_geometry(new, e)
+    assert np.abs(phi_new).max() < 1e-9 * ell.sum()
+    assert tpe.energy(new, e, 2.0, 4.5) == pytest.approx(info["E1"], rel=1e-14)
