@@ -1,0 +1,211 @@
+/*
+ * rcurves.h -- C ABI of librcurves.so, the MI355X (gfx950) hot path of
+ * "Repulsive Curves" (Yu, Schumacher, Crane): the discrete tangent-point
+ * energy and its differential, the fractional Sobolev-Slobodeckij operator
+ * A = B + B0, the constrained (projected) Sobolev gradient, the line-search
+ * step with constraint projection, and a Barnes-Hut far field.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Curves are graphs G = (V, E) with vertex coordinates gamma: V -> R^3
+ *   (paper Sec. 4, "Notation").  Edges are oriented pairs (i1, i2).
+ * - Vertex arrays (gamma, dE, X, Y, g) are DEVICE pointers to double
+ *   [n_vertices][3] (vertex-major, xyz interleaved).  The state is always
+ *   float64; `rc_dtype` selects the precision in which the pair kernels
+ *   evaluate the energy, the differential and the operator.
+ * - The caller allocates and owns every array it passes.  The library never
+ *   frees caller memory.  All workspace is allocated by rc_create and
+ *   released by rc_destroy.
+ * - Every call is ordered on the context's stream.  Calls whose results are
+ *   scalars needed for control flow (solver iterations, line search)
+ *   synchronise that stream internally; rc_energy, rc_differential and
+ *   rc_sobolev_apply do not synchronise.
+ * - Errors: argument and parameter errors are returned synchronously and
+ *   leave outputs untouched.  Every call returns RC_OK on success.
+ *   rc_last_error() gives a human-readable message for the last failure on
+ *   the calling thread.
+ * - One context per stream; contexts are independent and not thread-safe.
+ */
+#ifndef RCURVES_H
+#define RCURVES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rc_ctx rc_ctx;
+typedef void* rc_stream; /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+  RC_OK = 0,
+  RC_ERR_ARG = 1,           /* null pointer, bad size, bad index, bad enum */
+  RC_ERR_PARAM_RANGE = 2,   /* alpha <= 1 or beta outside [alpha+2, 2 alpha+1) (Lemma FiniteTangentPointEnergy) */
+  RC_ERR_DEGENERATE = 3,    /* zero-length edge, or coincident vertices of disjoint edges */
+  RC_ERR_NONFINITE = 4,     /* a result is Inf or NaN */
+  RC_ERR_NOT_CONVERGED = 5, /* iterative solve hit its iteration limit */
+  RC_ERR_PROJECTION = 6,    /* constraint projection did not reach its tolerance */
+  RC_ERR_LINESEARCH = 7,    /* no step length passed (projection + Armijo) */
+  RC_ERR_SINGULAR = 8,      /* a factorisation broke down */
+  RC_ERR_NOMEM = 9,
+  RC_ERR_HIP = 10,          /* a HIP runtime call failed */
+  RC_ERR_UNSUPPORTED = 11   /* topology or option the library does not handle */
+} rc_status;
+
+typedef enum { RC_F64 = 0, RC_F32 = 1 } rc_dtype;
+
+/* Constraint flags (paper Sec. 7.1). */
+enum {
+  RC_C_BARYCENTER = 1,   /* Phi = sum_I l_I (x_I - x0), 3 rows */
+  RC_C_TOTAL_LENGTH = 2, /* Phi = L0 - sum_I l_I, 1 row */
+  RC_C_EDGE_LENGTH = 4   /* Phi_I = l0_I - l_I, one row per edge */
+};
+
+/* Solver kinds for the projected Sobolev gradient (Sec. 4.3.1, App. B.3). */
+typedef enum {
+  RC_SOLVE_DENSE = 0,    /* assembled FP64 A, Cholesky of Abar + C^T C, Schur complement */
+  RC_SOLVE_PCG_JACOBI = 1, /* matrix-free projected PCG, Jacobi preconditioner */
+  RC_SOLVE_PCG_MG = 2    /* matrix-free projected PCG, multigrid V-cycle preconditioner */
+} rc_solver;
+
+typedef struct {
+  int32_t solver;        /* rc_solver */
+  double tol;            /* relative residual ||P(b - Abar x)|| / ||P b|| (FP64 true residual) */
+  int32_t max_iter;      /* PCG iterations (all restarts together) */
+  int32_t replace_every; /* FP64 true-residual replacement period (0 = only at convergence) */
+  int32_t mg_min_vertices; /* coarsest multigrid level size (vertices per loop, total) */
+  int32_t cheb_degree;   /* Chebyshev smoothing steps per V-cycle visit */
+  int32_t op_f64;        /* 1 = the PCG operator runs in FP64 even when dtype is F32 */
+} rc_solve_opts;
+
+typedef struct {
+  double c_armijo;       /* sufficient-decrease constant */
+  double shrink;         /* step shrink factor */
+  double tau0;           /* first step length (after normalising g) */
+  int32_t max_backtracks;
+  int32_t max_proj_iter; /* projection iterations per trial step */
+  double proj_tol;       /* relative projection tolerance (times mean edge length) */
+} rc_ls_opts;
+
+typedef struct {
+  double energy;         /* energy before the step */
+  double energy_new;     /* energy after the step */
+  double grad_norm;      /* Euclidean norm of the projected gradient */
+  double residual;       /* final relative FP64 residual of the gradient solve */
+  double tau;            /* accepted step length (0 if none) */
+  int32_t iterations;    /* PCG iterations of the gradient solve */
+  int32_t proj_solve_iterations; /* PCG iterations spent in projection solves */
+  int32_t backtracks;
+  int32_t proj_iters;    /* projection iterations at the accepted step */
+  int32_t status;        /* rc_status of the last call */
+  int32_t pad;
+} rc_stats;
+
+/* Default option values. */
+void rc_default_solve_opts(rc_solve_opts* o);
+void rc_default_ls_opts(rc_ls_opts* o);
+
+/* Last error message of the calling thread ("" if none). */
+const char* rc_last_error(void);
+
+/* Create a context for a curve network with n_vertices vertices and n_edges
+ * edges.  `edges_h` is a HOST array int32 [n_edges][2] of oriented edges
+ * (i1, i2), 0 <= i < n_vertices, i1 != i2 (paper Sec. 4, "Notation").
+ * alpha, beta: tangent-point exponents, alpha > 1, alpha + 2 <= beta < 2 alpha + 1
+ * (Lemma FiniteTangentPointEnergy; eq. TangentPointKernel).
+ * dtype: precision of the pair kernels.  stream: HIP stream for all work.
+ * Multigrid, edge-length constraints and dense assembly need every vertex to
+ * have degree <= 2 (loops and open paths); other graphs get RC_ERR_UNSUPPORTED
+ * from those calls only. */
+rc_status rc_create(int32_t n_vertices, int32_t n_edges, const int32_t* edges_h,
+                    double alpha, double beta, rc_dtype dtype, rc_stream stream,
+                    rc_ctx** out);
+rc_status rc_destroy(rc_ctx* ctx);
+
+/* Discrete energy (eqs. DiscreteEnergy, DiscreteKernel): the sum over ordered
+ * pairs of edges sharing no vertex of l_I l_J * 1/4 sum_{i in I, j in J} k(g_i, g_j, T_I).
+ * gamma: device double [nV][3].  energy: device double [1] (written). */
+rc_status rc_energy(rc_ctx* ctx, const double* gamma, double* energy);
+
+/* Energy and its exact differential dE = dE/dgamma (Sec. 4.1).
+ * dE: device double [nV][3] (written).  energy may be NULL. */
+rc_status rc_differential(rc_ctx* ctx, const double* gamma, double* energy, double* dE);
+
+/* Y = Abar X with A = B + B0 (eqs. DiscreteHighOrderPart, Sec. 4.2.3,
+ * eq. VectorInnerProduct), evaluated matrix-free from gamma in the context's
+ * dtype.  X, Y: device double [nV][3]; Y is overwritten. */
+rc_status rc_sobolev_apply(rc_ctx* ctx, const double* gamma, const double* X, double* Y);
+
+/* Same, with the precision chosen per call (RC_F64 or RC_F32). */
+rc_status rc_sobolev_apply_prec(rc_ctx* ctx, const double* gamma, const double* X, double* Y,
+                                rc_dtype prec);
+
+/* diag(A) (the Jacobi preconditioner): device double [nV] (written). */
+rc_status rc_sobolev_diag(rc_ctx* ctx, const double* gamma, double* diag);
+
+/* Dense A = B + B0 in FP64: device double [nV][nV] row-major (written).
+ * Needs vertex degree <= 2. */
+rc_status rc_assemble_dense(rc_ctx* ctx, const double* gamma, double* A);
+
+/* Choose the constraint set (bitwise OR of RC_C_*) and its targets.
+ * x0_h: HOST double[3] barycenter target, or NULL = the length-weighted
+ * barycenter of gamma_ref.  total_len0: target total length, or a negative
+ * value = that of gamma_ref.  edge_len0: DEVICE double [nE] target lengths,
+ * or NULL = those of gamma_ref.  gamma_ref: device double [nV][3]. */
+rc_status rc_set_constraints(rc_ctx* ctx, uint32_t mask, const double* gamma_ref,
+                             const double* x0_h, double total_len0, const double* edge_len0);
+
+/* Phi(gamma) (Sec. 7.1) in the row order barycenter (3), total length (1),
+ * edge lengths (nE), restricted to the active set.  phi: device double [k]. */
+rc_status rc_constraint_values(rc_ctx* ctx, const double* gamma, double* phi);
+
+/* Number of active constraint rows k. */
+int32_t rc_constraint_count(const rc_ctx* ctx);
+
+/* Y = P X with P = I - C^T (C C^T)^-1 C the Euclidean projector onto null(C),
+ * C = dPhi(gamma) (App. B.3.3, eq. ProjectedSystem).  X may equal Y. */
+rc_status rc_project(rc_ctx* ctx, const double* gamma, const double* X, double* Y);
+
+/* Projected Sobolev gradient: solve eq. GradientSaddlePointProblem
+ *   [Abar C^T; C 0] [g; lambda] = [dE; 0]
+ * (dense FP64, or projected PCG on P Abar P y = P dE, App. B.3.3).
+ * dE, g: device double [nV][3].  opts: host, NULL = defaults.
+ * stats: host, may be NULL (iterations, residual). */
+rc_status rc_sobolev_gradient(rc_ctx* ctx, const double* gamma, const double* dE, double* g,
+                              const rc_solve_opts* opts, rc_stats* stats);
+
+/* Backtracking step of Sec. 4.4 with the constraint projection of
+ * Sec. 4.3.2 (eq. ConstraintSaddlePointProblem, solved through eq.
+ * SaddleSolutionTransformation on the PCG paths): normalise g, start at
+ * tau0, shrink until projection succeeds and the Armijo condition holds at
+ * the projected curve.  gamma: device double [nV][3], updated in place on
+ * success (left unchanged on RC_ERR_LINESEARCH).  energy0: energy at gamma.
+ * tau_h: host, accepted step length. */
+rc_status rc_line_search_step(rc_ctx* ctx, double* gamma, double energy0, const double* dE,
+                              const double* g, const rc_ls_opts* ls, const rc_solve_opts* so,
+                              double* tau_h, rc_stats* stats);
+
+/* One projected Sobolev step: energy and differential, projected gradient,
+ * line search.  gamma is updated in place.  stats: host, may be NULL. */
+rc_status rc_step(rc_ctx* ctx, double* gamma, const rc_solve_opts* so, const rc_ls_opts* ls,
+                  rc_stats* stats);
+
+/* Barnes-Hut energy and differential (App. B.1): a BVH over the tangent-points
+ * (T_I, x_I) in R^6 built on the device, admissibility
+ * r_x < theta |x_I - xbar_B| and r_T < theta (eq. BarnesHutCondition), far
+ * field per eq. BVHNodeTPE, near field summed directly with the edge-midpoint
+ * rule.  FP32 arithmetic.  leaf_size: edges per leaf (<= 64).
+ * energy: device double [1]; dE: device double [nV][3]. */
+rc_status rc_bh_differential(rc_ctx* ctx, const double* gamma, double theta, int32_t leaf_size,
+                             double* energy, double* dE);
+
+/* Exact edge-midpoint energy and differential (the theta -> 0 limit of
+ * rc_bh_differential), in the context's dtype. */
+rc_status rc_midpoint_differential(rc_ctx* ctx, const double* gamma, double* energy, double* dE);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RCURVES_H */

@@ -1,0 +1,252 @@
+"""ctypes binding of librcurves.so (the C ABI declared in include/rcurves.h).
+
+Argument marshalling only: every function here checks tensor placement,
+dtype and shape, passes raw device pointers and the current HIP stream to
+the library, and turns a non-zero status into :class:`RcError`.  No compute
+happens in Python.  Loading fails loudly when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librcurves.so")
+
+RC_F64, RC_F32 = 0, 1
+RC_C_BARYCENTER, RC_C_TOTAL_LENGTH, RC_C_EDGE_LENGTH = 1, 2, 4
+RC_SOLVE_DENSE, RC_SOLVE_PCG_JACOBI, RC_SOLVE_PCG_MG = 0, 1, 2
+
+STATUS = {
+    0: "RC_OK", 1: "RC_ERR_ARG", 2: "RC_ERR_PARAM_RANGE", 3: "RC_ERR_DEGENERATE", 4: "RC_ERR_NONFINITE",
+    5: "RC_ERR_NOT_CONVERGED", 6: "RC_ERR_PROJECTION", 7: "RC_ERR_LINESEARCH", 8: "RC_ERR_SINGULAR",
+    9: "RC_ERR_NOMEM", 10: "RC_ERR_HIP", 11: "RC_ERR_UNSUPPORTED",
+}
+
+EXPORTED = [
+    "rc_default_solve_opts", "rc_default_ls_opts", "rc_last_error", "rc_create", "rc_destroy", "rc_energy",
+    "rc_differential", "rc_sobolev_apply", "rc_sobolev_apply_prec", "rc_sobolev_diag", "rc_assemble_dense",
+    "rc_set_constraints", "rc_constraint_values", "rc_constraint_count", "rc_project", "rc_sobolev_gradient",
+    "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_midpoint_differential",
+]
+
+
+class RcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("solver", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("replace_every", C.c_int32), ("mg_min_vertices", C.c_int32), ("cheb_degree", C.c_int32),
+                ("op_f64", C.c_int32)]
+
+
+class LsOpts(C.Structure):
+    _fields_ = [("c_armijo", C.c_double), ("shrink", C.c_double), ("tau0", C.c_double),
+                ("max_backtracks", C.c_int32), ("max_proj_iter", C.c_int32), ("proj_tol", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("energy", C.c_double), ("energy_new", C.c_double), ("grad_norm", C.c_double),
+                ("residual", C.c_double), ("tau", C.c_double), ("iterations", C.c_int32),
+                ("proj_solve_iterations", C.c_int32), ("backtracks", C.c_int32), ("proj_iters", C.c_int32),
+                ("status", C.c_int32), ("pad", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+_lib = None
+
+
+def load():
+    """Load librcurves.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, D, U32 = C.c_void_p, C.c_int32, C.c_double, C.c_uint32
+    sig = {
+        "rc_default_solve_opts": (None, [C.POINTER(SolveOpts)]),
+        "rc_default_ls_opts": (None, [C.POINTER(LsOpts)]),
+        "rc_last_error": (C.c_char_p, []),
+        "rc_create": (I32, [I32, I32, P, D, D, I32, P, C.POINTER(P)]),
+        "rc_destroy": (I32, [P]),
+        "rc_energy": (I32, [P, P, P]),
+        "rc_differential": (I32, [P, P, P, P]),
+        "rc_sobolev_apply": (I32, [P, P, P, P]),
+        "rc_sobolev_apply_prec": (I32, [P, P, P, P, I32]),
+        "rc_sobolev_diag": (I32, [P, P, P]),
+        "rc_assemble_dense": (I32, [P, P, P]),
+        "rc_set_constraints": (I32, [P, U32, P, P, D, P]),
+        "rc_constraint_values": (I32, [P, P, P]),
+        "rc_constraint_count": (I32, [P]),
+        "rc_project": (I32, [P, P, P, P]),
+        "rc_sobolev_gradient": (I32, [P, P, P, P, C.POINTER(SolveOpts), C.POINTER(Stats)]),
+        "rc_line_search_step": (I32, [P, P, D, P, P, C.POINTER(LsOpts), C.POINTER(SolveOpts), C.POINTER(D),
+                                      C.POINTER(Stats)]),
+        "rc_step": (I32, [P, P, C.POINTER(SolveOpts), C.POINTER(LsOpts), C.POINTER(Stats)]),
+        "rc_bh_differential": (I32, [P, P, D, I32, P, P]),
+        "rc_midpoint_differential": (I32, [P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        if not hasattr(lib, name):
+            continue
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != 0:
+        raise RcError(status, load().rc_last_error().decode())
+
+
+def _ptr(t, shape=None, dtype=None, name="tensor"):
+    import torch
+
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_solve_opts(**kw):
+    o = SolveOpts()
+    load().rc_default_solve_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def default_ls_opts(**kw):
+    o = LsOpts()
+    load().rc_default_ls_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """Owns one rc_ctx (one curve network) bound to the current stream."""
+
+    def __init__(self, n_vertices, edges, alpha, beta, dtype=RC_F32):
+        import torch
+
+        lib = load()
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32))
+        if e.ndim != 2 or e.shape[1] != 2:
+            raise ValueError("edges must be [n_edges, 2]")
+        self.nV, self.nE = int(n_vertices), int(e.shape[0])
+        self.alpha, self.beta, self.dtype = float(alpha), float(beta), int(dtype)
+        h = C.c_void_p()
+        _check(lib.rc_create(self.nV, self.nE, e.ctypes.data_as(C.c_void_p), self.alpha, self.beta, self.dtype,
+                             _stream(), C.byref(h)))
+        self.h = h
+        self._f64 = torch.float64
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().rc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _v(self, t, name):
+        return _ptr(t, (self.nV, 3), self._f64, name)
+
+    def rc_energy(self, gamma, energy):
+        _check(load().rc_energy(self.h, self._v(gamma, "gamma"), _ptr(energy, (1,), self._f64, "energy")))
+
+    def rc_differential(self, gamma, energy, dE):
+        _check(load().rc_differential(self.h, self._v(gamma, "gamma"), _ptr(energy, (1,), self._f64, "energy"),
+                                      self._v(dE, "dE")))
+
+    def rc_sobolev_apply(self, gamma, X, Y, prec=None):
+        if prec is None:
+            _check(load().rc_sobolev_apply(self.h, self._v(gamma, "gamma"), self._v(X, "X"), self._v(Y, "Y")))
+        else:
+            _check(load().rc_sobolev_apply_prec(self.h, self._v(gamma, "gamma"), self._v(X, "X"),
+                                                self._v(Y, "Y"), int(prec)))
+
+    def rc_sobolev_diag(self, gamma, diag):
+        _check(load().rc_sobolev_diag(self.h, self._v(gamma, "gamma"), _ptr(diag, (self.nV,), self._f64, "diag")))
+
+    def rc_assemble_dense(self, gamma, A):
+        _check(load().rc_assemble_dense(self.h, self._v(gamma, "gamma"),
+                                        _ptr(A, (self.nV, self.nV), self._f64, "A")))
+
+    def rc_set_constraints(self, mask, gamma_ref, x0=None, total_len0=-1.0, edge_len0=None):
+        x0p = None
+        if x0 is not None:
+            self._x0 = (C.c_double * 3)(*[float(v) for v in x0])
+            x0p = C.cast(self._x0, C.c_void_p)
+        _check(load().rc_set_constraints(self.h, int(mask), self._v(gamma_ref, "gamma_ref"), x0p,
+                                         float(total_len0), _ptr(edge_len0, (self.nE,), self._f64, "edge_len0")))
+
+    def rc_constraint_count(self):
+        return int(load().rc_constraint_count(self.h))
+
+    def rc_constraint_values(self, gamma, phi):
+        _check(load().rc_constraint_values(self.h, self._v(gamma, "gamma"),
+                                           _ptr(phi, (self.rc_constraint_count(),), self._f64, "phi")))
+
+    def rc_project(self, gamma, X, Y):
+        _check(load().rc_project(self.h, self._v(gamma, "gamma"), self._v(X, "X"), self._v(Y, "Y")))
+
+    def rc_sobolev_gradient(self, gamma, dE, g, opts=None):
+        st = Stats()
+        o = opts if opts is not None else default_solve_opts()
+        _check(load().rc_sobolev_gradient(self.h, self._v(gamma, "gamma"), self._v(dE, "dE"), self._v(g, "g"),
+                                          C.byref(o), C.byref(st)))
+        return st.as_dict()
+
+    def rc_line_search_step(self, gamma, energy0, dE, g, ls=None, so=None):
+        st = Stats()
+        tau = C.c_double(0.0)
+        l = ls if ls is not None else default_ls_opts()
+        o = so if so is not None else default_solve_opts()
+        _check(load().rc_line_search_step(self.h, self._v(gamma, "gamma"), float(energy0), self._v(dE, "dE"),
+                                          self._v(g, "g"), C.byref(l), C.byref(o), C.byref(tau), C.byref(st)))
+        return tau.value, st.as_dict()
+
+    def rc_step(self, gamma, so=None, ls=None):
+        st = Stats()
+        o = so if so is not None else default_solve_opts()
+        l = ls if ls is not None else default_ls_opts()
+        _check(load().rc_step(self.h, self._v(gamma, "gamma"), C.byref(o), C.byref(l), C.byref(st)))
+        return st.as_dict()
+
+    def rc_bh_differential(self, gamma, theta, leaf_size, energy, dE):
+        _check(load().rc_bh_differential(self.h, self._v(gamma, "gamma"), float(theta), int(leaf_size),
+                                         _ptr(energy, (1,), self._f64, "energy"), self._v(dE, "dE")))
+
+    def rc_midpoint_differential(self, gamma, energy, dE):
+        _check(load().rc_midpoint_differential(self.h, self._v(gamma, "gamma"),
+                                               _ptr(energy, (1,), self._f64, "energy"), self._v(dE, "dE")))

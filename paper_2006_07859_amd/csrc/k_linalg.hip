@@ -1,0 +1,617 @@
+// FP64 vector, dense and constraint kernels used by the solvers.
+//
+// Reductions are two-pass (per-block partials, then one block) in a fixed
+// order, so every result is bitwise reproducible.
+
+#include "rc_internal.h"
+#include "k_linalg.h"
+
+#include <algorithm>
+
+namespace rc {
+
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+constexpr int kRedBlocks = 240;
+
+// ---------------------------------------------------------------------------
+// vectors
+// ---------------------------------------------------------------------------
+__global__ void k_axpby(double a, const double* __restrict__ x, double b, double* __restrict__ y, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+void vec_axpby(double a, const double* x, double b, double* y, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(cdiv(n, 256)), dim3(256), 0, s, a, x, b, y, n);
+}
+
+void vec_copy(const double* x, double* y, int n, hipStream_t s) {
+  hipMemcpyAsync(y, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+}
+
+__global__ void k_diag_inv(const double* __restrict__ r, const double* __restrict__ d, double* __restrict__ z,
+                           int nV) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 3 * nV) z[i] = r[i] / d[i / 3];
+}
+
+void vec_scale_diag_inv(const double* r, const double* d, double* z, int nV, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_inv, dim3(cdiv(3 * nV, 256)), dim3(256), 0, s, r, d, z, nV);
+}
+
+// Batched dots: out[r] = X_r . Y_r for r < m, X_r = X + r*ldx, Y_r = Y + r*ldy
+// (ldy = 0 dots every X_r with the same Y).  grid = (kRedBlocks, m).
+__global__ void k_dot_partial(const double* __restrict__ X, int ldx, const double* __restrict__ Y, int ldy, int n,
+                              double* __restrict__ partial) {
+  __shared__ double sm[256];
+  const double* x = X + (size_t)blockIdx.y * ldx;
+  const double* y = Y + (size_t)blockIdx.y * ldy;
+  double v = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) v += x[i] * y[i];
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = sm[0];
+}
+
+__global__ void k_dot_final(const double* __restrict__ partial, int nb, double* __restrict__ out) {
+  __shared__ double sm[256];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) v += partial[(size_t)blockIdx.x * nb + i];
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+}
+
+void vec_dot(const double* x, const double* y, int n, double* scratch, double* result, hipStream_t s) {
+  vec_dots(x, 0, y, 0, n, 1, scratch, result, s);
+}
+
+void vec_dots(const double* X, int ldx, const double* Y, int ldy, int n, int m, double* scratch, double* out,
+              hipStream_t s) {
+  int nb = std::min(kRedBlocks, std::max(1, cdiv(n, 256)));
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb, m), dim3(256), 0, s, X, ldx, Y, ldy, n, scratch);
+  hipLaunchKernelGGL(k_dot_final, dim3(m), dim3(256), 0, s, scratch, nb, out);
+}
+
+int dot_scratch_size(int m) { return kRedBlocks * m; }
+
+// ---------------------------------------------------------------------------
+// blocked dense Cholesky (lower, row-major, in place), block size 32
+// ---------------------------------------------------------------------------
+constexpr int kNB = 32;
+
+__global__ void k_potrf_diag(double* __restrict__ A, int n, int k0, int* __restrict__ info) {
+  __shared__ double L[kNB][kNB + 1];
+  const int nb = min(kNB, n - k0);
+  const int tid = threadIdx.x;  // 256 threads
+  for (int idx = tid; idx < nb * nb; idx += 256) {
+    int i = idx / nb, j = idx % nb;
+    L[i][j] = A[(size_t)(k0 + i) * n + k0 + j];
+  }
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    if (tid == 0) {
+      double d = L[k][k];
+      if (!(d > 0.0)) {
+        if (info[0] == 0) info[0] = k0 + k + 1;
+        d = 1.0;
+      }
+      L[k][k] = sqrt(d);
+    }
+    __syncthreads();
+    const double piv = L[k][k];
+    for (int i = k + 1 + tid; i < nb; i += 256) L[i][k] /= piv;
+    __syncthreads();
+    for (int idx = tid; idx < (nb - k - 1) * (nb - k - 1); idx += 256) {
+      int i = k + 1 + idx / (nb - k - 1), j = k + 1 + idx % (nb - k - 1);
+      if (j <= i) L[i][j] -= L[i][k] * L[j][k];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < nb * nb; idx += 256) {
+    int i = idx / nb, j = idx % nb;
+    A[(size_t)(k0 + i) * n + k0 + j] = (j <= i) ? L[i][j] : 0.0;
+  }
+}
+
+// Rows below the diagonal block: A[i, k0:k0+nb] <- A[i, k0:k0+nb] L_kk^-T.
+// One thread per row; 64 rows per block.
+__global__ void k_trsm_panel(double* __restrict__ A, int n, int k0) {
+  __shared__ double L[kNB][kNB + 1];
+  const int nb = min(kNB, n - k0);
+  for (int idx = threadIdx.x; idx < nb * nb; idx += blockDim.x) {
+    int i = idx / nb, j = idx % nb;
+    L[i][j] = A[(size_t)(k0 + i) * n + k0 + j];
+  }
+  __syncthreads();
+  const int i = k0 + nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x[kNB];
+  for (int j = 0; j < nb; ++j) x[j] = A[(size_t)i * n + k0 + j];
+  for (int j = 0; j < nb; ++j) {
+    double v = x[j];
+    for (int p = 0; p < j; ++p) v -= x[p] * L[j][p];
+    x[j] = v / L[j][j];
+  }
+  for (int j = 0; j < nb; ++j) A[(size_t)i * n + k0 + j] = x[j];
+}
+
+// Trailing update A[i,j] -= sum_p A[i,k0+p] A[j,k0+p] for i >= j >= k1 = k0+nb.
+// 32x32 output tiles, 256 threads, each 4 outputs.
+__global__ void k_syrk_update(double* __restrict__ A, int n, int k0) {
+  const int nb = min(kNB, n - k0);
+  const int k1 = k0 + nb;
+  const int ti = blockIdx.y, tj = blockIdx.x;
+  if (tj > ti) return;
+  const int i0 = k1 + ti * 32, j0 = k1 + tj * 32;
+  __shared__ double Pi[32][kNB + 1], Pj[32][kNB + 1];
+  for (int idx = threadIdx.x; idx < 32 * nb; idx += 256) {
+    int r = idx / nb, p = idx % nb;
+    Pi[r][p] = (i0 + r < n) ? A[(size_t)(i0 + r) * n + k0 + p] : 0.0;
+    Pj[r][p] = (j0 + r < n) ? A[(size_t)(j0 + r) * n + k0 + p] : 0.0;
+  }
+  __syncthreads();
+  for (int q = 0; q < 4; ++q) {
+    int idx = threadIdx.x + 256 * q;
+    int r = idx / 32, cc = idx % 32;
+    int i = i0 + r, j = j0 + cc;
+    if (i >= n || j >= n || j > i) continue;
+    double s = 0.0;
+    for (int p = 0; p < nb; ++p) s += Pi[r][p] * Pj[cc][p];
+    A[(size_t)i * n + j] -= s;
+  }
+}
+
+void dense_cholesky(double* A, int n, int* info, hipStream_t s) {
+  hipMemsetAsync(info, 0, sizeof(int), s);
+  for (int k0 = 0; k0 < n; k0 += kNB) {
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, n, k0, info);
+    const int rest = n - k0 - kNB;
+    if (rest <= 0) break;
+    hipLaunchKernelGGL(k_trsm_panel, dim3(cdiv(rest, 64)), dim3(64), 0, s, A, n, k0);
+    const int nt = cdiv(rest, 32);
+    hipLaunchKernelGGL(k_syrk_update, dim3(nt, nt), dim3(256), 0, s, A, n, k0);
+  }
+}
+
+// L L^T X = B, B is n x m row-major, one workgroup, column sweeps.
+__global__ void k_chol_solve(const double* __restrict__ L, double* __restrict__ B, int n, int m) {
+  // forward: L y = b
+  for (int j = 0; j < n; ++j) {
+    const double ljj = L[(size_t)j * n + j];
+    for (int c = threadIdx.x; c < m; c += blockDim.x) B[(size_t)j * m + c] /= ljj;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < (n - j - 1) * m; idx += blockDim.x) {
+      int i = j + 1 + idx / m, c = idx % m;
+      B[(size_t)i * m + c] -= L[(size_t)i * n + j] * B[(size_t)j * m + c];
+    }
+    __syncthreads();
+  }
+  // backward: L^T x = y
+  for (int j = n - 1; j >= 0; --j) {
+    const double ljj = L[(size_t)j * n + j];
+    for (int c = threadIdx.x; c < m; c += blockDim.x) B[(size_t)j * m + c] /= ljj;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < j * m; idx += blockDim.x) {
+      int i = idx / m, c = idx % m;
+      B[(size_t)i * m + c] -= L[(size_t)j * n + i] * B[(size_t)j * m + c];
+    }
+    __syncthreads();
+  }
+}
+
+void dense_chol_solve(const double* L, double* B, int n, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, s, L, B, n, m);
+}
+
+// C[m x n] = op(A) B + beta C, A is m x k (or k x m if transA), B is k x n, row-major.
+__global__ void k_gemm(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C, int m,
+                       int n, int k, double beta, int transA) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= m || j >= n) return;
+  double s = 0.0;
+  if (transA)
+    for (int p = 0; p < k; ++p) s += A[(size_t)p * m + i] * B[(size_t)p * n + j];
+  else
+    for (int p = 0; p < k; ++p) s += A[(size_t)i * k + p] * B[(size_t)p * n + j];
+  C[(size_t)i * n + j] = s + (beta != 0.0 ? beta * C[(size_t)i * n + j] : 0.0);
+}
+
+void dense_gemm(const double* A, const double* B, double* C, int m, int n, int k, double beta, bool transA,
+                hipStream_t s) {
+  dim3 b(16, 16), g(cdiv(n, 16), cdiv(m, 16));
+  hipLaunchKernelGGL(k_gemm, g, b, 0, s, A, B, C, m, n, k, beta, transA ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// tridiagonal solve: partition method in one workgroup
+// ---------------------------------------------------------------------------
+// Rows k < n: a[k] y[k-1] + d[k] y[k] + c[k] y[k+1] = b[k], with a[0] = c[n-1] = 0
+// (zero couplings also separate independent segments).  The rows are split
+// into nc chunks; each thread eliminates its chunk for the right-hand side
+// and the two coupling spikes, thread 0 solves the 2-unknowns-per-chunk
+// reduced system, and every thread then back-substitutes its chunk.
+constexpr int kTriThreads = 256;
+
+__global__ __launch_bounds__(kTriThreads) void k_tridiag(const double* __restrict__ a, const double* __restrict__ d,
+                                                         const double* __restrict__ c, const double* __restrict__ b,
+                                                         double* __restrict__ y, int n, double* __restrict__ G,
+                                                         double* __restrict__ Vs, double* __restrict__ Ws,
+                                                         double* __restrict__ Cp) {
+  __shared__ double sF[kTriThreads], sGl[kTriThreads];
+  __shared__ double rF[3][kTriThreads], rG[3][kTriThreads];  // (g, v, w) at chunk first/last rows
+  const int nc = max(1, min(kTriThreads, n / 8));
+  const int j = threadIdx.x;
+  if (j < nc) {
+    const int k0 = (int)(((long long)j * n) / nc), k1 = (int)(((long long)(j + 1) * n) / nc);
+    double cp = 0.0, gp = 0.0, vp = 0.0, wp = 0.0;
+    for (int k = k0; k < k1; ++k) {
+      const double ak = (k == k0) ? 0.0 : a[k];
+      const double den = d[k] - ak * cp;
+      const double inv = 1.0 / den;
+      const double vin = (k == k0) ? a[k] : 0.0;
+      const double win = (k == k1 - 1) ? c[k] : 0.0;
+      gp = (b[k] - ak * gp) * inv;
+      vp = (vin - ak * vp) * inv;
+      wp = (win - ak * wp) * inv;
+      cp = (k == k1 - 1) ? 0.0 : c[k] * inv;
+      Cp[k] = cp;
+      G[k] = gp;
+      Vs[k] = vp;
+      Ws[k] = wp;
+    }
+    double gn = 0.0, vn = 0.0, wn = 0.0;
+    for (int k = k1 - 1; k >= k0; --k) {
+      const double cpk = Cp[k];
+      gn = G[k] - cpk * gn;
+      vn = Vs[k] - cpk * vn;
+      wn = Ws[k] - cpk * wn;
+      G[k] = gn;
+      Vs[k] = vn;
+      Ws[k] = wn;
+    }
+    rF[0][j] = G[k0]; rF[1][j] = Vs[k0]; rF[2][j] = Ws[k0];
+    rG[0][j] = G[k1 - 1]; rG[1][j] = Vs[k1 - 1]; rG[2][j] = Ws[k1 - 1];
+  }
+  __syncthreads();
+  if (j == 0) {
+    // F_j = gF - vF G_{j-1} - wF F_{j+1};  G_j = gG - vG G_{j-1} - wG F_{j+1}
+    double al = 0.0, be = 0.0;  // G_{j-1} = al + be F_j
+    for (int q = 0; q < nc; ++q) {
+      const double den = 1.0 + rF[1][q] * be;
+      const double phi = (rF[0][q] - rF[1][q] * al) / den;
+      const double psi = -rF[2][q] / den;
+      const double na = rG[0][q] - rG[1][q] * (al + be * phi);
+      const double nbv = -rG[1][q] * be * psi - rG[2][q];
+      sF[q] = phi;   // F_q = phi + psi F_{q+1}
+      sGl[q] = psi;
+      rG[0][q] = na;  // G_q = na + nb F_{q+1}
+      rG[1][q] = nbv;
+      al = na;
+      be = nbv;
+    }
+    double Fn = 0.0;
+    for (int q = nc - 1; q >= 0; --q) {
+      const double Fq = sF[q] + sGl[q] * Fn;
+      const double Gq = rG[0][q] + rG[1][q] * Fn;
+      sF[q] = Fq;
+      sGl[q] = Gq;
+      Fn = Fq;
+    }
+  }
+  __syncthreads();
+  if (j < nc) {
+    const int k0 = (int)(((long long)j * n) / nc), k1 = (int)(((long long)(j + 1) * n) / nc);
+    const double GL = (j > 0) ? sGl[j - 1] : 0.0;
+    const double FR = (j + 1 < nc) ? sF[j + 1] : 0.0;
+    for (int k = k0; k < k1; ++k) y[k] = G[k] - Vs[k] * GL - Ws[k] * FR;
+  }
+}
+
+void tridiag_solve(const double* a, const double* d, const double* c, const double* b, double* y, int n,
+                   double* scratch4n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kTriThreads), 0, s, a, d, c, b, y, n, scratch4n, scratch4n + n,
+                     scratch4n + 2 * n, scratch4n + 3 * n);
+}
+
+// ---------------------------------------------------------------------------
+// constraints (FP64): Jacobian products for the edge rows and the dense
+// border rows (barycenter, total length, one cut edge per loop)
+// ---------------------------------------------------------------------------
+// Edge-length row I (Phi_I = l0_I - l_I): +T_I at i1, -T_I at i2.
+// Path rows are the edge rows except the cut edges, in chain order: path_edge[k].
+
+// Geometry in FP64 for the constraint kernels: l, T, x per edge.
+__global__ void k_cons_geom(const double* __restrict__ gamma, const int2* __restrict__ edges, int nE,
+                            double* __restrict__ geo /* [nE][8]: l, T(3), x(3), - */) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nE) return;
+  int2 e = edges[I];
+  double p[3], q[3];
+  for (int k = 0; k < 3; ++k) {
+    p[k] = gamma[3 * e.x + k];
+    q[k] = gamma[3 * e.y + k];
+  }
+  double d0 = q[0] - p[0], d1 = q[1] - p[1], d2 = q[2] - p[2];
+  double l = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  double* o = geo + 8 * (size_t)I;
+  o[0] = l;
+  o[1] = d0 / l;
+  o[2] = d1 / l;
+  o[3] = d2 / l;
+  o[4] = 0.5 * (p[0] + q[0]);
+  o[5] = 0.5 * (p[1] + q[1]);
+  o[6] = 0.5 * (p[2] + q[2]);
+  o[7] = 0.0;
+}
+
+void cons_geometry(const double* gamma, const int2* edges, int nE, double* geo, hipStream_t s) {
+  hipLaunchKernelGGL(k_cons_geom, dim3(cdiv(nE, 256)), dim3(256), 0, s, gamma, edges, nE, geo);
+}
+
+// Per-edge values summed by the border-row evaluations, stored as four
+// columns vals[c * nE + I]: l_I (x_I - x0)_c for c < 3 and l_I for c = 3.
+__global__ void k_cons_phi_edge(const double* __restrict__ geo, const double* __restrict__ x0, int nE,
+                                const double* __restrict__ len0, double* __restrict__ vals,
+                                double* __restrict__ phi_edges) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nE) return;
+  const double* g = geo + 8 * (size_t)I;
+  vals[I] = g[0] * (g[4] - x0[0]);
+  vals[nE + I] = g[0] * (g[5] - x0[1]);
+  vals[2 * (size_t)nE + I] = g[0] * (g[6] - x0[2]);
+  vals[3 * (size_t)nE + I] = g[0];
+  if (phi_edges) phi_edges[I] = len0[I] - g[0];
+}
+
+void cons_phi_edge(const double* geo, const double* x0, int nE, const double* len0, double* vals,
+                   double* phi_edges, hipStream_t s) {
+  hipLaunchKernelGGL(k_cons_phi_edge, dim3(cdiv(nE, 256)), dim3(256), 0, s, geo, x0, nE, len0, vals, phi_edges);
+}
+
+// Border rows as dense vertex vectors rows[r][nV][3].
+//   barycenter row c: at v, sum_{I at v} (l_I/2) e_c + sigma_I(v) (x_I - x0)_c T_I, sigma(i1) = -1, sigma(i2) = +1
+//   total-length row: at v, sum_{I at v} s_I(v) T_I with s(i1) = +1, s(i2) = -1
+//   cut-edge row for edge I: +T_I at i1, -T_I at i2
+__global__ void k_border_rows(const double* __restrict__ geo, const int* __restrict__ inc_off,
+                              const int* __restrict__ inc, const double* __restrict__ x0, int nV, int bary,
+                              int total, double* __restrict__ rows) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nV) return;
+  double M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double L[3] = {0, 0, 0};
+  for (int k = inc_off[v]; k < inc_off[v + 1]; ++k) {
+    const int I = inc[k] >> 1;
+    const double sg = (inc[k] & 1) ? 1.0 : -1.0;  // sigma
+    const double* g = geo + 8 * (size_t)I;
+    for (int r = 0; r < 3; ++r) {
+      M[r][r] += 0.5 * g[0];
+      for (int cc = 0; cc < 3; ++cc) M[r][cc] += sg * (g[4 + r] - x0[r]) * g[1 + cc];
+      L[r] += -sg * g[1 + r];
+    }
+  }
+  int row = 0;
+  if (bary) {
+    for (int r = 0; r < 3; ++r) {
+      for (int cc = 0; cc < 3; ++cc) rows[((size_t)row * nV + v) * 3 + cc] = M[r][cc];
+      ++row;
+    }
+  }
+  if (total) {
+    for (int cc = 0; cc < 3; ++cc) rows[((size_t)row * nV + v) * 3 + cc] = L[cc];
+    ++row;
+  }
+}
+
+__global__ void k_cut_rows(const double* __restrict__ geo, const int2* __restrict__ edges,
+                           const int* __restrict__ cut_edge, int ncut, int row0, int nV, double* __restrict__ rows) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ncut) return;
+  const int I = cut_edge[q];
+  const double* g = geo + 8 * (size_t)I;
+  double* r = rows + (size_t)(row0 + q) * nV * 3;
+  int2 e = edges[I];
+  for (int cc = 0; cc < 3; ++cc) {
+    r[3 * e.x + cc] = g[1 + cc];
+    r[3 * e.y + cc] = -g[1 + cc];
+  }
+}
+
+void cons_border_rows(const double* geo, const int* inc_off, const int* inc, const int2* edges, const double* x0,
+                      int nV, int bary, int total, const int* cut_edge, int ncut, double* rows, int nrows,
+                      hipStream_t s) {
+  hipMemsetAsync(rows, 0, sizeof(double) * (size_t)nrows * nV * 3, s);
+  hipLaunchKernelGGL(k_border_rows, dim3(cdiv(nV, 256)), dim3(256), 0, s, geo, inc_off, inc, x0, nV, bary, total,
+                     rows);
+  if (ncut > 0)
+    hipLaunchKernelGGL(k_cut_rows, dim3(cdiv(ncut, 256)), dim3(256), 0, s, geo, edges, cut_edge, ncut,
+                       3 * bary + total, nV, rows);
+}
+
+// Tridiagonal coefficients of C_p C_p^T over the path rows (chain order):
+// diag 2, off-diagonal s_I(v) s_J(v) T_I.T_J for consecutive rows sharing v.
+__global__ void k_path_coeffs(const double* __restrict__ geo, const int2* __restrict__ edges,
+                              const int* __restrict__ path_edge, const int* __restrict__ path_prev, int np,
+                              double* __restrict__ ta, double* __restrict__ td, double* __restrict__ tc) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= np) return;
+  td[k] = 2.0;
+  const int I = path_edge[k];
+  if (path_prev[k]) {
+    const int J = path_edge[k - 1];
+    int2 ei = edges[I], ej = edges[J];
+    // shared vertex and the signs (+1 at i1, -1 at i2)
+    double si, sj;
+    if (ei.x == ej.x) { si = 1; sj = 1; }
+    else if (ei.x == ej.y) { si = 1; sj = -1; }
+    else if (ei.y == ej.x) { si = -1; sj = 1; }
+    else { si = -1; sj = -1; }
+    const double* gi = geo + 8 * (size_t)I;
+    const double* gj = geo + 8 * (size_t)J;
+    const double v = si * sj * (gi[1] * gj[1] + gi[2] * gj[2] + gi[3] * gj[3]);
+    ta[k] = v;
+    tc[k - 1] = v;
+  } else {
+    ta[k] = 0.0;
+  }
+  if (k == np - 1) tc[k] = 0.0;
+}
+
+void cons_path_coeffs(const double* geo, const int2* edges, const int* path_edge, const int* path_prev, int np,
+                      double* ta, double* td, double* tc, hipStream_t s) {
+  // tc[k-1] is written by row k; rows without a predecessor leave tc[k-1] to be zero
+  hipMemsetAsync(tc, 0, sizeof(double) * np, s);
+  hipLaunchKernelGGL(k_path_coeffs, dim3(cdiv(np, 256)), dim3(256), 0, s, geo, edges, path_edge, path_prev, np,
+                     ta, td, tc);
+}
+
+// w[k] = C_{path_edge[k]} v = T_I . (v_i1 - v_i2), for m vectors (v_r = V + r*3nV, w_r = W + r*np).
+__global__ void k_path_apply(const double* __restrict__ geo, const int2* __restrict__ edges,
+                             const int* __restrict__ path_edge, int np, const double* __restrict__ V, int nV,
+                             double* __restrict__ W) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= np) return;
+  const double* v = V + (size_t)blockIdx.y * 3 * nV;
+  const int I = path_edge[k];
+  const int2 e = edges[I];
+  const double* g = geo + 8 * (size_t)I;
+  W[(size_t)blockIdx.y * np + k] =
+      g[1] * (v[3 * e.x] - v[3 * e.y]) + g[2] * (v[3 * e.x + 1] - v[3 * e.y + 1]) + g[3] * (v[3 * e.x + 2] - v[3 * e.y + 2]);
+}
+
+void cons_path_apply(const double* geo, const int2* edges, const int* path_edge, int np, const double* V, int nV,
+                     int m, double* W, hipStream_t s) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_path_apply, dim3(cdiv(np, 256), m), dim3(256), 0, s, geo, edges, path_edge, np, V, nV, W);
+}
+
+// out_v = alpha * in_v - [ sum_{path rows k at v} s(v) T_I y_k + sum_r yb[r] rows[r][v] ]
+// (in may be null: out = -C^T y).
+__global__ void k_apply_CT(const double* __restrict__ geo, const int* __restrict__ inc_off,
+                           const int* __restrict__ inc, const int* __restrict__ edge_path_row,
+                           const double* __restrict__ yp, const double* __restrict__ rows,
+                           const double* __restrict__ yb, int nb, int nV, const double* __restrict__ in,
+                           double* __restrict__ out) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nV) return;
+  double acc[3] = {0, 0, 0};
+  for (int k = inc_off[v]; k < inc_off[v + 1]; ++k) {
+    const int I = inc[k] >> 1;
+    const int pr = edge_path_row[I];
+    if (pr < 0) continue;
+    const double sg = (inc[k] & 1) ? -1.0 : 1.0;
+    const double* g = geo + 8 * (size_t)I;
+    for (int cc = 0; cc < 3; ++cc) acc[cc] += sg * g[1 + cc] * yp[pr];
+  }
+  for (int r = 0; r < nb; ++r)
+    for (int cc = 0; cc < 3; ++cc) acc[cc] += yb[r] * rows[((size_t)r * nV + v) * 3 + cc];
+  for (int cc = 0; cc < 3; ++cc) out[3 * v + cc] = (in ? in[3 * v + cc] : 0.0) - acc[cc];
+}
+
+void cons_apply_CT(const double* geo, const int* inc_off, const int* inc, const int* edge_path_row,
+                   const double* yp, const double* rows, const double* yb, int nb, int nV, const double* in,
+                   double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_apply_CT, dim3(cdiv(nV, 256)), dim3(256), 0, s, geo, inc_off, inc, edge_path_row, yp, rows,
+                     yb, nb, nV, in, out);
+}
+
+// y_p -= Z y_b (Z is np x nb column blocks: Z + r*np), and the small dense
+// border solve y_b = Sinv rhs_b, done by one thread (nb is small).
+__global__ void k_border_solve(const double* __restrict__ Sinv, const double* __restrict__ rhs, int nb,
+                               double* __restrict__ yb) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = 0; i < nb; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < nb; ++j) s += Sinv[i * nb + j] * rhs[j];
+    yb[i] = s;
+  }
+}
+
+__global__ void k_sub_Zy(const double* __restrict__ Z, const double* __restrict__ yb, int nb, int np,
+                         double* __restrict__ yp) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= np) return;
+  double s = 0.0;
+  for (int r = 0; r < nb; ++r) s += Z[(size_t)r * np + k] * yb[r];
+  yp[k] -= s;
+}
+
+__global__ void k_rhs_border(const double* __restrict__ wb, const double* __restrict__ dots, int nb,
+                             double* __restrict__ rhs) {
+  for (int r = threadIdx.x; r < nb; r += blockDim.x) rhs[r] = wb[r] - dots[r];
+}
+
+void cons_border_solve(const double* Sinv, const double* wb, const double* dots, double* rhs, int nb, double* yb,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs_border, dim3(1), dim3(64), 0, s, wb, dots, nb, rhs);
+  hipLaunchKernelGGL(k_border_solve, dim3(1), dim3(64), 0, s, Sinv, rhs, nb, yb);
+}
+
+void cons_sub_Zy(const double* Z, const double* yb, int nb, int np, double* yp, hipStream_t s) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_sub_Zy, dim3(cdiv(np, 256)), dim3(256), 0, s, Z, yb, nb, np, yp);
+}
+
+// ---------------------------------------------------------------------------
+// misc small kernels for the solvers
+// ---------------------------------------------------------------------------
+// gamma_out = gamma - tau * g / gnorm   (gnorm read on device)
+__global__ void k_trial(const double* __restrict__ gamma, const double* __restrict__ g, const double* __restrict__ gg,
+                        double tau, double* __restrict__ out, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = gamma[i] - tau * g[i] / sqrt(gg[0]);
+}
+
+void vec_trial(const double* gamma, const double* g, const double* gg, double tau, double* out, int n,
+               hipStream_t s) {
+  hipLaunchKernelGGL(k_trial, dim3(cdiv(n, 256)), dim3(256), 0, s, gamma, g, gg, tau, out, n);
+}
+
+// Dense Abar + C^T C for the direct path: H[3v+a][3w+b] = A[v][w] delta_ab + sum_r C[r][3v+a] C[r][3w+b].
+__global__ void k_build_H(const double* __restrict__ A, const double* __restrict__ CtC, int nV,
+                          double* __restrict__ H) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.y * blockDim.y + threadIdx.y;
+  int n = 3 * nV;
+  if (i >= n || j >= n) return;
+  double v = CtC[(size_t)i * n + j];
+  if (i % 3 == j % 3) v += A[(size_t)(i / 3) * nV + j / 3];
+  H[(size_t)i * n + j] = v;
+}
+
+void dense_build_H(const double* A, const double* CtC, int nV, double* H, hipStream_t s) {
+  int n = 3 * nV;
+  dim3 b(16, 16), g(cdiv(n, 16), cdiv(n, 16));
+  hipLaunchKernelGGL(k_build_H, g, b, 0, s, A, CtC, nV, H);
+}
+
+// Dense constraint matrix in the external row order (bary, total, edges) from
+// the border rows and the edge rows: Cd[k][3 nV].
+__global__ void k_dense_C_edges(const double* __restrict__ geo, const int2* __restrict__ edges, int nE, int row0,
+                                int nV, double* __restrict__ Cd) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nE) return;
+  const double* g = geo + 8 * (size_t)I;
+  int2 e = edges[I];
+  double* r = Cd + (size_t)(row0 + I) * 3 * nV;
+  for (int cc = 0; cc < 3; ++cc) {
+    r[3 * e.x + cc] = g[1 + cc];
+    r[3 * e.y + cc] = -g[1 + cc];
+  }
+}
+
+void dense_C_edges(const double* geo, const int2* edges, int nE, int row0, int nV, double* Cd, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_C_edges, dim3(cdiv(nE, 256)), dim3(256), 0, s, geo, edges, nE, row0, nV, Cd);
+}
+
+}  // namespace rc

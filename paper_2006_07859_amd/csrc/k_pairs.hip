@@ -1,0 +1,910 @@
+// Pair kernels of the tangent-point hot path on gfx950.
+//
+// Every kernel here is a gather over ordered edge pairs (I, J): a thread owns
+// one target edge I, the block's 256 targets sweep a range of source edges J
+// that is staged through LDS in tiles of 256, and each thread accumulates its
+// target's sums in registers.  Sources are split into `nchunk` ranges along
+// blockIdx.y so that a launch has thousands of workgroups; per-chunk partial
+// sums land in a [chunk][slot][edge] buffer that a finalize kernel reduces in
+// FP64, in a fixed order (no atomics, bitwise reproducible).
+//
+// In FP32 the per-thread sums are kept in float over 64 sources at a time and
+// then folded into FP64 accumulators, so the long sums over all sources are
+// compensated blockwise.
+//
+// Edge pairs that share a vertex (I = J included) are omitted, as the
+// discrete energy (Sec. 4.1, eq. DiscreteEnergy) and the Gram matrices
+// (Sec. 4.2) prescribe.  Such a pair gets weight 0 and its coincident vertex
+// pairs get a stand-in distance of 1, so no Inf or NaN is formed.
+
+#include <type_traits>
+
+#include "rc_internal.h"
+
+namespace rc {
+
+// ---------------------------------------------------------------------------
+// math helpers: hardware transcendentals in FP32, library ones in FP64
+// ---------------------------------------------------------------------------
+template <typename R> __device__ __forceinline__ R f_rsq(R x);
+template <> __device__ __forceinline__ float f_rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ __forceinline__ double f_rsq<double>(double x) { return rsqrt(x); }
+template <typename R> __device__ __forceinline__ R f_sqrt(R x);
+template <> __device__ __forceinline__ float f_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> __device__ __forceinline__ double f_sqrt<double>(double x) { return sqrt(x); }
+template <typename R> __device__ __forceinline__ R f_exp2(R x);
+template <> __device__ __forceinline__ float f_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
+template <> __device__ __forceinline__ double f_exp2<double>(double x) { return exp2(x); }
+template <typename R> __device__ __forceinline__ R f_log2(R x);
+template <> __device__ __forceinline__ float f_log2<float>(float x) { return __builtin_amdgcn_logf(x); }
+template <> __device__ __forceinline__ double f_log2<double>(double x) { return log2(x); }
+
+// r2^(-beta/2) from rs = 1/sqrt(r2) and ri = 1/r2.
+template <int EC, typename R>
+__device__ __forceinline__ R pow_beta(R r2, R rs, R ri, R half_beta) {
+  if constexpr (EC == kA2B4) return ri * ri;
+  else if constexpr (EC == kA2B45) return ri * ri * f_sqrt<R>(rs);
+  else if constexpr (EC == kA3B6) return ri * ri * ri;
+  else return f_exp2<R>(-half_beta * f_log2<R>(r2));
+}
+
+// ca = c^(alpha/2) and f = (alpha/2) c^(alpha/2 - 1) for c = |T x d|^2 >= 0.
+template <int EC, typename R>
+__device__ __forceinline__ void pow_alpha(R c, R half_alpha, R& ca, R& f) {
+  if constexpr (EC == kA2B4 || EC == kA2B45) {
+    ca = c;
+    f = R(1);
+  } else if constexpr (EC == kA3B6) {
+    R sq = f_sqrt<R>(c);
+    ca = c * sq;
+    f = R(1.5) * sq;
+  } else {
+    if (c > R(0)) {
+      ca = f_exp2<R>(half_alpha * f_log2<R>(c));
+      f = half_alpha * ca / c;
+    } else {
+      ca = R(0);
+      f = R(0);
+    }
+  }
+}
+
+// r2^(-(2 sigma + 1)/2): the weight exponent of B and B0 (Sec. 4.2.2-4.2.3).
+template <int EC, typename R>
+__device__ __forceinline__ R pow_sigma(R r2, R rs, R ri, R half_expo) {
+  if constexpr (EC == kA2B4) return ri;                       // 2 sigma + 1 = 2
+  else if constexpr (EC == kA2B45) return ri * f_sqrt<R>(rs);  // 2.5
+  else return f_exp2<R>(-half_expo * f_log2<R>(r2));          // 7/3 for (3,6), general
+}
+
+template <typename R>
+__device__ __forceinline__ R cross_norm2(R tx, R ty, R tz, R dx, R dy, R dz) {
+  // |T x d|^2 from the cross product itself: accurate when d is nearly
+  // parallel to T, where |d|^2 - (T.d)^2 would cancel catastrophically.
+  R cx = ty * dz - tz * dy;
+  R cy = tz * dx - tx * dz;
+  R cz = tx * dy - ty * dx;
+  return cx * cx + cy * cy + cz * cz;
+}
+
+ExpCase exp_case(double alpha, double beta) {
+  if (alpha == 2.0 && beta == 4.0) return kA2B4;
+  if (alpha == 2.0 && beta == 4.5) return kA2B45;
+  if (alpha == 3.0 && beta == 6.0) return kA3B6;
+  return kGeneral;
+}
+
+// ---------------------------------------------------------------------------
+// edge geometry: FP64 state -> rounded SoA in the kernel precision
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_geometry(const double* __restrict__ gamma, const int2* __restrict__ edges, int nE,
+                           V4<R>* __restrict__ A, V4<R>* __restrict__ B, V4<R>* __restrict__ T) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nE) return;
+  int2 e = edges[I];
+  double p0 = gamma[3 * e.x], p1 = gamma[3 * e.x + 1], p2 = gamma[3 * e.x + 2];
+  double q0 = gamma[3 * e.y], q1 = gamma[3 * e.y + 1], q2 = gamma[3 * e.y + 2];
+  double d0 = q0 - p0, d1 = q1 - p1, d2 = q2 - p2;
+  double l = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  double il = 1.0 / l;
+  A[I] = V4<R>{R(p0), R(p1), R(p2), R(l)};
+  B[I] = V4<R>{R(q0), R(q1), R(q2), R(0)};
+  T[I] = V4<R>{R(d0 * il), R(d1 * il), R(d2 * il), R(0)};
+}
+
+// ---------------------------------------------------------------------------
+// energy and differential, trapezoid rule over the four vertex pairs
+// ---------------------------------------------------------------------------
+// Accumulator slots (per target edge I; every term carries w = l_J / 4):
+//  0 E    sum k(d, T_I)                                  -> energy l_I * E
+//  1 S    sum k(d, T_I) + k(d, T_J)                      -> dl_I term
+//  2-4 G1 sum over (i1, j_b) of grad_d[k_I + k_J] minus its T_I part
+//  5-7 G2 same for i2
+//  8 Gt1, 9 Gt2: coefficient of T_I in those gradients
+//  10-12 Hd, 13 Ht: dk/dT_I projected on the tangent plane = -2 (Hd - Ht T_I)
+template <typename R, int EC, bool GRAD>
+struct TpeAcc {
+  R v[GRAD ? kTpeSlots : 1];
+};
+
+template <typename R, int EC, bool GRAD>
+__device__ __forceinline__ void tpe_vertex_pair(
+    R px, R py, R pz, R tIx, R tIy, R tIz,                // target vertex, T_I
+    R qx, R qy, R qz, R tJx, R tJy, R tJz,                // source vertex, T_J
+    bool same, R w, R half_alpha, R half_beta, R beta,
+    R& E, R& S, R& Gx, R& Gy, R& Gz, R& Gt, R& Hx, R& Hy, R& Hz, R& Ht) {
+  R dx = px - qx, dy = py - qy, dz = pz - qz;
+  R r2 = dx * dx + dy * dy + dz * dz;
+  r2 = same ? R(1) : r2;
+  R rs = f_rsq<R>(r2);
+  R ri = rs * rs;
+  R rbw = pow_beta<EC, R>(r2, rs, ri, half_beta) * w;
+  R cI = cross_norm2<R>(tIx, tIy, tIz, dx, dy, dz);
+  R caI, fI;
+  pow_alpha<EC, R>(cI, half_alpha, caI, fI);
+  R kI = caI * rbw;
+  E += kI;
+  if constexpr (GRAD) {
+    R cJ = cross_norm2<R>(tJx, tJy, tJz, dx, dy, dz);
+    R caJ, fJ;
+    pow_alpha<EC, R>(cJ, half_alpha, caJ, fJ);
+    R kJ = caJ * rbw;
+    R ks = kI + kJ;
+    S += ks;
+    R tI = tIx * dx + tIy * dy + tIz * dz;
+    R tJ = tJx * dx + tJy * dy + tJz * dz;
+    R gI = R(2) * fI * rbw;
+    R gJ = R(2) * fJ * rbw;
+    // grad_d k = 2 f rb (d - t T) - beta k d / r2
+    R c1 = gI + gJ - beta * ks * ri;
+    R c2 = gJ * tJ;
+    Gx += c1 * dx - c2 * tJx;
+    Gy += c1 * dy - c2 * tJy;
+    Gz += c1 * dz - c2 * tJz;
+    Gt += gI * tI;
+    // dk/dT_I on the tangent plane: -2 f rb t (d - t T_I)
+    R c3 = fI * rbw * tI;
+    Hx += c3 * dx;
+    Hy += c3 * dy;
+    Hz += c3 * dz;
+    Ht += c3 * tI;
+  }
+}
+
+// Chain-near test: edges of the same chain at most kBand apart (cyclically on loops).
+__device__ __forceinline__ bool chain_near(int4 ci, int4 cj) {
+  int dd = abs(cj.y - ci.y);
+  dd = ci.w ? min(dd, ci.z - dd) : dd;
+  return (cj.x == ci.x) & (dd <= kBand);
+}
+
+// BAND: the graph is a union of chains and the kernel runs in FP32; pairs
+// that are chain-near (which include every pair sharing a vertex) are left
+// to the FP64 near-band kernel.  Otherwise only pairs sharing a vertex are
+// skipped.
+template <typename R, int EC, bool GRAD, bool BAND>
+__global__ __launch_bounds__(kTile) void k_tpe_pairs(
+    const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB, const V4<R>* __restrict__ GT,
+    const int2* __restrict__ edges, const int4* __restrict__ cinfo, int nE, int src_per_chunk, R half_alpha,
+    R half_beta, R beta, double* __restrict__ part) {
+  __shared__ V4<R> sA[kTile], sB[kTile], sT[kTile];
+  __shared__ int2 sE[kTile];
+  __shared__ int4 sC[BAND ? kTile : 1];
+  const int tid = threadIdx.x;
+  const int I = blockIdx.x * kTile + tid;
+  const bool act = I < nE;
+  const int Ic = act ? I : nE - 1;
+  const V4<R> a = GA[Ic], b = GB[Ic], t = GT[Ic];
+  const int2 ei = act ? edges[Ic] : make_int2(-1, -2);
+  int4 ci = make_int4(-1, 0, 0, 0);
+  if constexpr (BAND) ci = act ? cinfo[Ic] : make_int4(-1, 0, 0, 0);
+  constexpr int NS = GRAD ? kTpeSlots : 1;
+  double acc[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+
+  const int s0 = blockIdx.y * src_per_chunk;
+  const int s1 = min(nE, s0 + src_per_chunk);
+  for (int t0 = s0; t0 < s1; t0 += kTile) {
+    __syncthreads();
+    if (t0 + tid < s1) {
+      sA[tid] = GA[t0 + tid];
+      sB[tid] = GB[t0 + tid];
+      sT[tid] = GT[t0 + tid];
+      sE[tid] = edges[t0 + tid];
+      if constexpr (BAND) sC[tid] = cinfo[t0 + tid];
+    }
+    __syncthreads();
+    const int cnt = min(kTile, s1 - t0);
+    for (int u0 = 0; u0 < cnt; u0 += kSub) {
+      const int u1 = min(cnt, u0 + kSub);
+      R E = 0, S = 0, G1x = 0, G1y = 0, G1z = 0, G2x = 0, G2y = 0, G2z = 0;
+      R Gt1 = 0, Gt2 = 0, Hx = 0, Hy = 0, Hz = 0, Ht = 0;
+      for (int u = u0; u < u1; ++u) {
+        const V4<R> qa = sA[u], qb = sB[u], qt = sT[u];
+        bool s11, s12, s21, s22, skip;
+        if constexpr (BAND) {
+          skip = chain_near(ci, sC[u]);
+          s11 = s12 = s21 = s22 = skip;
+        } else {
+          const int2 ej = sE[u];
+          s11 = ei.x == ej.x;
+          s12 = ei.x == ej.y;
+          s21 = ei.y == ej.x;
+          s22 = ei.y == ej.y;
+          skip = s11 | s12 | s21 | s22;
+        }
+        const R w = skip ? R(0) : R(0.25) * qa.w;
+        tpe_vertex_pair<R, EC, GRAD>(a.x, a.y, a.z, t.x, t.y, t.z, qa.x, qa.y, qa.z, qt.x, qt.y, qt.z,
+                                     s11, w, half_alpha, half_beta, beta, E, S, G1x, G1y, G1z, Gt1,
+                                     Hx, Hy, Hz, Ht);
+        tpe_vertex_pair<R, EC, GRAD>(a.x, a.y, a.z, t.x, t.y, t.z, qb.x, qb.y, qb.z, qt.x, qt.y, qt.z,
+                                     s12, w, half_alpha, half_beta, beta, E, S, G1x, G1y, G1z, Gt1,
+                                     Hx, Hy, Hz, Ht);
+        tpe_vertex_pair<R, EC, GRAD>(b.x, b.y, b.z, t.x, t.y, t.z, qa.x, qa.y, qa.z, qt.x, qt.y, qt.z,
+                                     s21, w, half_alpha, half_beta, beta, E, S, G2x, G2y, G2z, Gt2,
+                                     Hx, Hy, Hz, Ht);
+        tpe_vertex_pair<R, EC, GRAD>(b.x, b.y, b.z, t.x, t.y, t.z, qb.x, qb.y, qb.z, qt.x, qt.y, qt.z,
+                                     s22, w, half_alpha, half_beta, beta, E, S, G2x, G2y, G2z, Gt2,
+                                     Hx, Hy, Hz, Ht);
+      }
+      acc[0] += (double)E;
+      if constexpr (GRAD) {
+        acc[1] += (double)S;
+        acc[2] += (double)G1x; acc[3] += (double)G1y; acc[4] += (double)G1z;
+        acc[5] += (double)G2x; acc[6] += (double)G2y; acc[7] += (double)G2z;
+        acc[8] += (double)Gt1; acc[9] += (double)Gt2;
+        acc[10] += (double)Hx; acc[11] += (double)Hy; acc[12] += (double)Hz; acc[13] += (double)Ht;
+      }
+    }
+  }
+  if (act) {
+    double* out = part + (size_t)blockIdx.y * NS * nE + I;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) out[(size_t)k * nE] = acc[k];
+  }
+}
+
+// FP64 near band: for target I, every source J of the same chain at most
+// kBand apart (the pairs the BAND pair kernel skips), with the exact
+// shared-vertex exclusion.  Writes the partial-sum chunk `chunk`.
+template <int EC, bool GRAD>
+__global__ void k_tpe_band(const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB,
+                           const V4<double>* __restrict__ GT, const int2* __restrict__ edges,
+                           const int4* __restrict__ cinfo, const int* __restrict__ chain_edge, int nE,
+                           double half_alpha, double half_beta, double beta, int chunk, double* __restrict__ part) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nE) return;
+  const V4<double> a = GA[I], b = GB[I], t = GT[I];
+  const int2 ei = edges[I];
+  const int4 ci = cinfo[I];
+  const int m = ci.z;
+  int q0, q1;
+  if (ci.w && m <= 2 * kBand + 1) {
+    q0 = 0;
+    q1 = m - 1;
+  } else if (ci.w) {
+    q0 = ci.y - kBand;
+    q1 = ci.y + kBand;
+  } else {
+    q0 = max(0, ci.y - kBand);
+    q1 = min(m - 1, ci.y + kBand);
+  }
+  double E = 0, S = 0, G1x = 0, G1y = 0, G1z = 0, G2x = 0, G2y = 0, G2z = 0;
+  double Gt1 = 0, Gt2 = 0, Hx = 0, Hy = 0, Hz = 0, Ht = 0;
+  for (int q = q0; q <= q1; ++q) {
+    const int qq = ((q % m) + m) % m;
+    const int J = chain_edge[ci.x + qq];
+    const int2 ej = edges[J];
+    const bool s11 = ei.x == ej.x, s12 = ei.x == ej.y, s21 = ei.y == ej.x, s22 = ei.y == ej.y;
+    if (s11 | s12 | s21 | s22) continue;
+    const V4<double> qa = GA[J], qb = GB[J], qt = GT[J];
+    const double w = 0.25 * qa.w;
+    tpe_vertex_pair<double, EC, GRAD>(a.x, a.y, a.z, t.x, t.y, t.z, qa.x, qa.y, qa.z, qt.x, qt.y, qt.z, false, w,
+                                      half_alpha, half_beta, beta, E, S, G1x, G1y, G1z, Gt1, Hx, Hy, Hz, Ht);
+    tpe_vertex_pair<double, EC, GRAD>(a.x, a.y, a.z, t.x, t.y, t.z, qb.x, qb.y, qb.z, qt.x, qt.y, qt.z, false, w,
+                                      half_alpha, half_beta, beta, E, S, G1x, G1y, G1z, Gt1, Hx, Hy, Hz, Ht);
+    tpe_vertex_pair<double, EC, GRAD>(b.x, b.y, b.z, t.x, t.y, t.z, qa.x, qa.y, qa.z, qt.x, qt.y, qt.z, false, w,
+                                      half_alpha, half_beta, beta, E, S, G2x, G2y, G2z, Gt2, Hx, Hy, Hz, Ht);
+    tpe_vertex_pair<double, EC, GRAD>(b.x, b.y, b.z, t.x, t.y, t.z, qb.x, qb.y, qb.z, qt.x, qt.y, qt.z, false, w,
+                                      half_alpha, half_beta, beta, E, S, G2x, G2y, G2z, Gt2, Hx, Hy, Hz, Ht);
+  }
+  constexpr int NS = GRAD ? kTpeSlots : 1;
+  double* out = part + (size_t)chunk * NS * nE + I;
+  out[0] = E;
+  if constexpr (GRAD) {
+    const double v[kTpeSlots] = {E, S, G1x, G1y, G1z, G2x, G2y, G2z, Gt1, Gt2, Hx, Hy, Hz, Ht};
+    for (int k = 1; k < kTpeSlots; ++k) out[(size_t)k * nE] = v[k];
+  }
+}
+
+// Sum the chunks and turn the accumulators into per-edge energy and endpoint
+// partials: edge_out[I] = (E_I, dE/dg_i1 (3), dE/dg_i2 (3), -).
+__global__ void k_tpe_finalize(const double* __restrict__ part, int nchunk, int nE, int grad,
+                               const double* __restrict__ gd_a, const double* __restrict__ gd_t,
+                               double* __restrict__ edge_out) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nE) return;
+  const int NS = grad ? kTpeSlots : 1;
+  double s[kTpeSlots];
+  for (int k = 0; k < NS; ++k) {
+    double v = 0.0;
+    for (int c = 0; c < nchunk; ++c) v += part[((size_t)c * NS + k) * nE + I];
+    s[k] = v;
+  }
+  const double l = gd_a[4 * I + 3];
+  double* o = edge_out + 8 * (size_t)I;
+  o[0] = l * s[0];
+  if (!grad) return;
+  const double Tx = gd_t[4 * I], Ty = gd_t[4 * I + 1], Tz = gd_t[4 * I + 2];
+  const double S = s[1];
+  const double Hx = s[10] - s[13] * Tx, Hy = s[11] - s[13] * Ty, Hz = s[12] - s[13] * Tz;
+  o[1] = -Tx * S + l * (s[2] - s[8] * Tx) + 2.0 * Hx;
+  o[2] = -Ty * S + l * (s[3] - s[8] * Ty) + 2.0 * Hy;
+  o[3] = -Tz * S + l * (s[4] - s[8] * Tz) + 2.0 * Hz;
+  o[4] = Tx * S + l * (s[5] - s[9] * Tx) - 2.0 * Hx;
+  o[5] = Ty * S + l * (s[6] - s[9] * Ty) - 2.0 * Hy;
+  o[6] = Tz * S + l * (s[7] - s[9] * Tz) - 2.0 * Hz;
+}
+
+// dE_v = sum over incident (edge, endpoint) of the edge's endpoint partial.
+__global__ void k_gather_vertex(const double* __restrict__ edge_out, const int* __restrict__ inc_off,
+                                const int* __restrict__ inc, int nV, double* __restrict__ dE) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nV) return;
+  double gx = 0, gy = 0, gz = 0;
+  for (int k = inc_off[v]; k < inc_off[v + 1]; ++k) {
+    int code = inc[k];
+    const double* o = edge_out + 8 * (size_t)(code >> 1) + 1 + 3 * (code & 1);
+    gx += o[0];
+    gy += o[1];
+    gz += o[2];
+  }
+  dE[3 * v] = gx;
+  dE[3 * v + 1] = gy;
+  dE[3 * v + 2] = gz;
+}
+
+// Deterministic sum of edge_out[8 I + slot] over I: per-block partials, then one block.
+__global__ void k_sum_slot(const double* __restrict__ edge_out, int slot, int n, double* __restrict__ partial) {
+  __shared__ double sm[256];
+  double v = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) v += edge_out[8 * (size_t)i + slot];
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
+}
+
+__global__ void k_sum_partials(const double* __restrict__ partial, int n, double* __restrict__ out) {
+  __shared__ double sm[256];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) v += partial[i];
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+static void sum_edge_slot(const Curve& c, int slot, double* out, hipStream_t s) {
+  int nb = c.red_blocks;
+  hipLaunchKernelGGL(k_sum_slot, dim3(nb), dim3(256), 0, s, c.edge_out, slot, c.nE, c.red);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, c.red, nb, out);
+}
+
+// ---------------------------------------------------------------------------
+// Sobolev operator A = B + B0, matrix-free (gather form of the increment tables)
+// ---------------------------------------------------------------------------
+// Per RHS component u (three at once), per edge J:
+//   s_J = (u_j2 - u_j1) / l_J  (D_J u = s_J T_J),   ubar_J = (u_j1 + u_j2) / 2.
+// For target I, with rho = |g_ia - g_jb|^-(2 sigma + 1) and c_X = |T_X x d|^2:
+//   Wq = sum_J l_J sum_ab rho               Q = sum_J l_J sum_ab rho <T_I,T_J> s_J
+//   P0 = sum_J l_J sum_ab rho (c_I + c_J) / r^4      P = same weights times ubar_J
+// then  q_I = l_I/2 (Wq s_I - Q)  and  p_I = l_I/4 (P0 ubar_I - P)  and
+//   (B u)_i2 += q_I / l_I, (B u)_i1 -= q_I / l_I, (B0 u)_i1,i2 += p_I / 2,
+// which is the printed increment table summed over J.  The diagonal of A is
+//   diag_v = sum_{I at v} Wq_I / (2 l_I) + l_I P0_I / 16.
+template <typename R>
+__global__ void k_edge_rhs(const double* __restrict__ X, const int2* __restrict__ edges, int nE,
+                           V4<R>* __restrict__ Sout, V4<R>* __restrict__ Uout) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nE) return;
+  int2 e = edges[I];
+  double ax = X[3 * e.x], ay = X[3 * e.x + 1], az = X[3 * e.x + 2];
+  double bx = X[3 * e.y], by = X[3 * e.y + 1], bz = X[3 * e.y + 2];
+  Sout[I] = V4<R>{R(bx - ax), R(by - ay), R(bz - az), R(0)};  // divided by l in the finalize / kernel
+  Uout[I] = V4<R>{R(0.5 * (ax + bx)), R(0.5 * (ay + by)), R(0.5 * (az + bz)), R(0)};
+}
+
+template <typename R, int EC>
+__global__ __launch_bounds__(kTile) void k_sob_pairs(
+    const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB, const V4<R>* __restrict__ GT,
+    const int2* __restrict__ edges, const V4<R>* __restrict__ RS, const V4<R>* __restrict__ RU,
+    int nE, int src_per_chunk, R half_expo, double* __restrict__ part) {
+  __shared__ V4<R> sA[kTile], sB[kTile], sT[kTile], sS[kTile], sU[kTile];
+  __shared__ int2 sE[kTile];
+  const int tid = threadIdx.x;
+  const int I = blockIdx.x * kTile + tid;
+  const bool act = I < nE;
+  const int Ic = act ? I : nE - 1;
+  const V4<R> a = GA[Ic], b = GB[Ic], t = GT[Ic];
+  const int2 ei = act ? edges[Ic] : make_int2(-1, -2);
+  double acc[kSobSlots];
+#pragma unroll
+  for (int k = 0; k < kSobSlots; ++k) acc[k] = 0.0;
+  const int s0 = blockIdx.y * src_per_chunk;
+  const int s1 = min(nE, s0 + src_per_chunk);
+  for (int t0 = s0; t0 < s1; t0 += kTile) {
+    __syncthreads();
+    if (t0 + tid < s1) {
+      const int j = t0 + tid;
+      V4<R> ga = GA[j], gs = RS[j];
+      const R il = R(1) / ga.w;
+      sA[tid] = ga;
+      sB[tid] = GB[j];
+      sT[tid] = GT[j];
+      sS[tid] = V4<R>{gs.x * il, gs.y * il, gs.z * il, R(0)};
+      sU[tid] = RU[j];
+      sE[tid] = edges[j];
+    }
+    __syncthreads();
+    const int cnt = min(kTile, s1 - t0);
+    for (int u0 = 0; u0 < cnt; u0 += kSub) {
+      const int u1 = min(cnt, u0 + kSub);
+      R Wq = 0, Qx = 0, Qy = 0, Qz = 0, P0 = 0, Px = 0, Py = 0, Pz = 0;
+      for (int u = u0; u < u1; ++u) {
+        const V4<R> qa = sA[u], qb = sB[u], qt = sT[u];
+        const int2 ej = sE[u];
+        const bool s11 = ei.x == ej.x, s12 = ei.x == ej.y, s21 = ei.y == ej.x, s22 = ei.y == ej.y;
+        const R w = (s11 | s12 | s21 | s22) ? R(0) : qa.w;
+        R rho = 0, rho0 = 0;
+#define RC_SOB_VP(PX, QX, SAME)                                                    \
+  {                                                                                \
+    R dx = PX.x - QX.x, dy = PX.y - QX.y, dz = PX.z - QX.z;                       \
+    R r2 = dx * dx + dy * dy + dz * dz;                                            \
+    r2 = (SAME) ? R(1) : r2;                                                       \
+    R rs = f_rsq<R>(r2);                                                           \
+    R ri = rs * rs;                                                                \
+    R p = pow_sigma<EC, R>(r2, rs, ri, half_expo);                                 \
+    R cI = cross_norm2<R>(t.x, t.y, t.z, dx, dy, dz);                              \
+    R cJ = cross_norm2<R>(qt.x, qt.y, qt.z, dx, dy, dz);                           \
+    rho += p;                                                                      \
+    rho0 += p * (cI + cJ) * ri * ri;                                               \
+  }
+        RC_SOB_VP(a, qa, s11)
+        RC_SOB_VP(a, qb, s12)
+        RC_SOB_VP(b, qa, s21)
+        RC_SOB_VP(b, qb, s22)
+#undef RC_SOB_VP
+        const V4<R> sj = sS[u], uj = sU[u];
+        const R wr = w * rho, w0 = w * rho0;
+        const R tt = wr * (t.x * qt.x + t.y * qt.y + t.z * qt.z);
+        Wq += wr;
+        Qx += tt * sj.x;
+        Qy += tt * sj.y;
+        Qz += tt * sj.z;
+        P0 += w0;
+        Px += w0 * uj.x;
+        Py += w0 * uj.y;
+        Pz += w0 * uj.z;
+      }
+      acc[0] += (double)Wq; acc[1] += (double)Qx; acc[2] += (double)Qy; acc[3] += (double)Qz;
+      acc[4] += (double)P0; acc[5] += (double)Px; acc[6] += (double)Py; acc[7] += (double)Pz;
+    }
+  }
+  if (act) {
+    double* out = part + (size_t)blockIdx.y * kSobSlots * nE + I;
+#pragma unroll
+    for (int k = 0; k < kSobSlots; ++k) out[(size_t)k * nE] = acc[k];
+  }
+}
+
+// Per edge: endpoint contributions of B u + B0 u (3 comps each) and the
+// diagonal pieces.  edge_out[I] = (y_i1 (3), y_i2 (3), dg_B, dg_B0).
+__global__ void k_sob_finalize(const double* __restrict__ part, int nchunk, int nE,
+                               const double* __restrict__ X, const int2* __restrict__ edges,
+                               double* __restrict__ edge_out) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nE) return;
+  double s[kSobSlots];
+  for (int k = 0; k < kSobSlots; ++k) {
+    double v = 0.0;
+    for (int c = 0; c < nchunk; ++c) v += part[((size_t)c * kSobSlots + k) * nE + I];
+    s[k] = v;
+  }
+  int2 e = edges[I];
+  double a[3], b[3];
+  for (int k = 0; k < 3; ++k) {
+    a[k] = X[3 * e.x + k];
+    b[k] = X[3 * e.y + k];
+  }
+  double* o = edge_out + 8 * (size_t)I;
+  // o[6], o[7] hold l_I on entry (written by the launcher's length kernel)
+  const double l = o[7];
+  const double il = 1.0 / l;
+  for (int k = 0; k < 3; ++k) {
+    const double sI = (b[k] - a[k]) * il;
+    const double uI = 0.5 * (a[k] + b[k]);
+    const double qoverl = 0.5 * (s[0] * sI - s[1 + k]);  // q_I / l_I
+    const double phalf = 0.125 * l * (s[4] * uI - s[5 + k]);  // p_I / 2
+    o[k] = -qoverl + phalf;
+    o[3 + k] = qoverl + phalf;
+  }
+  o[6] = s[0] * il * 0.5 + l * s[4] * (1.0 / 16.0);
+}
+
+template <typename R>
+__global__ void k_edge_length(const V4<R>* __restrict__ GA, int nE, double* __restrict__ edge_out) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I < nE) edge_out[8 * (size_t)I + 7] = (double)GA[I].w;
+}
+
+__global__ void k_gather_sob(const double* __restrict__ edge_out, const int* __restrict__ inc_off,
+                             const int* __restrict__ inc, int nV, double* __restrict__ Y,
+                             double* __restrict__ diag) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nV) return;
+  double y0 = 0, y1 = 0, y2 = 0, dg = 0;
+  for (int k = inc_off[v]; k < inc_off[v + 1]; ++k) {
+    int code = inc[k];
+    const double* o = edge_out + 8 * (size_t)(code >> 1);
+    const double* oy = o + 3 * (code & 1);
+    y0 += oy[0];
+    y1 += oy[1];
+    y2 += oy[2];
+    dg += o[6];
+  }
+  if (Y) {
+    Y[3 * v] = y0;
+    Y[3 * v + 1] = y1;
+    Y[3 * v + 2] = y2;
+  }
+  if (diag) diag[v] = dg;
+}
+
+// ---------------------------------------------------------------------------
+// edge-midpoint energy and differential (the sum Barnes-Hut approximates)
+// ---------------------------------------------------------------------------
+// Per target I with d = x_I - x_J and weights l_J:
+//  0 E = sum l_J k(d, T_I); 1 S = sum l_J (k_I + k_J); 2-4 G = sum l_J grad_d(k_I + k_J)
+//  minus its T_I part, 5 Gt; 6-8 Hd, 9 Ht as in the trapezoid kernel.
+constexpr int kMidSlotsUsed = 10;
+
+template <typename R, int EC>
+__global__ __launch_bounds__(kTile) void k_mid_pairs(
+    const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB, const V4<R>* __restrict__ GT,
+    const int2* __restrict__ edges, int nE, int src_per_chunk, R half_alpha, R half_beta, R beta,
+    double* __restrict__ part) {
+  __shared__ V4<R> sX[kTile], sT[kTile];
+  __shared__ int2 sE[kTile];
+  const int tid = threadIdx.x;
+  const int I = blockIdx.x * kTile + tid;
+  const bool act = I < nE;
+  const int Ic = act ? I : nE - 1;
+  const V4<R> a = GA[Ic], b = GB[Ic], t = GT[Ic];
+  const R mx = R(0.5) * (a.x + b.x), my = R(0.5) * (a.y + b.y), mz = R(0.5) * (a.z + b.z);
+  const int2 ei = act ? edges[Ic] : make_int2(-1, -2);
+  double acc[kMidSlotsUsed];
+#pragma unroll
+  for (int k = 0; k < kMidSlotsUsed; ++k) acc[k] = 0.0;
+  const int s0 = blockIdx.y * src_per_chunk;
+  const int s1 = min(nE, s0 + src_per_chunk);
+  for (int t0 = s0; t0 < s1; t0 += kTile) {
+    __syncthreads();
+    if (t0 + tid < s1) {
+      const int j = t0 + tid;
+      V4<R> ga = GA[j], gb = GB[j];
+      sX[tid] = V4<R>{R(0.5) * (ga.x + gb.x), R(0.5) * (ga.y + gb.y), R(0.5) * (ga.z + gb.z), ga.w};
+      sT[tid] = GT[j];
+      sE[tid] = edges[j];
+    }
+    __syncthreads();
+    const int cnt = min(kTile, s1 - t0);
+    for (int u0 = 0; u0 < cnt; u0 += kSub) {
+      const int u1 = min(cnt, u0 + kSub);
+      R E = 0, S = 0, Gx = 0, Gy = 0, Gz = 0, Gt = 0, Hx = 0, Hy = 0, Hz = 0, Ht = 0;
+      for (int u = u0; u < u1; ++u) {
+        const V4<R> q = sX[u], qt = sT[u];
+        const int2 ej = sE[u];
+        const bool excl = (ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y);
+        const R w = excl ? R(0) : q.w;
+        tpe_vertex_pair<R, EC, true>(mx, my, mz, t.x, t.y, t.z, q.x, q.y, q.z, qt.x, qt.y, qt.z,
+                                     ei.x == ej.x && ei.y == ej.y, w, half_alpha, half_beta, beta,
+                                     E, S, Gx, Gy, Gz, Gt, Hx, Hy, Hz, Ht);
+      }
+      acc[0] += (double)E; acc[1] += (double)S; acc[2] += (double)Gx; acc[3] += (double)Gy;
+      acc[4] += (double)Gz; acc[5] += (double)Gt; acc[6] += (double)Hx; acc[7] += (double)Hy;
+      acc[8] += (double)Hz; acc[9] += (double)Ht;
+    }
+  }
+  if (act) {
+    double* out = part + (size_t)blockIdx.y * kMidSlotsUsed * nE + I;
+#pragma unroll
+    for (int k = 0; k < kMidSlotsUsed; ++k) out[(size_t)k * nE] = acc[k];
+  }
+}
+
+__global__ void k_mid_finalize(const double* __restrict__ part, int nchunk, int nE,
+                               const double* __restrict__ gd_a, const double* __restrict__ gd_t,
+                               double* __restrict__ edge_out) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nE) return;
+  double s[kMidSlotsUsed];
+  for (int k = 0; k < kMidSlotsUsed; ++k) {
+    double v = 0.0;
+    for (int c = 0; c < nchunk; ++c) v += part[((size_t)c * kMidSlotsUsed + k) * nE + I];
+    s[k] = v;
+  }
+  const double l = gd_a[4 * I + 3];
+  const double Tx = gd_t[4 * I], Ty = gd_t[4 * I + 1], Tz = gd_t[4 * I + 2];
+  const double S = s[1];
+  const double Hx = s[6] - s[9] * Tx, Hy = s[7] - s[9] * Ty, Hz = s[8] - s[9] * Tz;
+  const double px = 0.5 * l * (s[2] - s[5] * Tx), py = 0.5 * l * (s[3] - s[5] * Ty),
+               pz = 0.5 * l * (s[4] - s[5] * Tz);
+  double* o = edge_out + 8 * (size_t)I;
+  o[0] = l * s[0];
+  o[1] = -Tx * S + px + 2.0 * Hx;
+  o[2] = -Ty * S + py + 2.0 * Hy;
+  o[3] = -Tz * S + pz + 2.0 * Hz;
+  o[4] = Tx * S + px - 2.0 * Hx;
+  o[5] = Ty * S + py - 2.0 * Hy;
+  o[6] = Tz * S + pz - 2.0 * Hz;
+}
+
+// ---------------------------------------------------------------------------
+// dense FP64 assembly (vertex-pair gather of the increment tables), degree <= 2
+// ---------------------------------------------------------------------------
+// Off-diagonal entry (v, w):
+//   sum over disjoint I at v, J at w of
+//      -2 s_I(v) s_J(w) w_IJ <T_I,T_J> / (l_I l_J) - (w0_IJ + w0_JI) / 4
+//   plus, when v and w are the two ends of an edge K,
+//      -Wq_K / (2 l_K) + l_K P0_K / 16
+// with s(i1) = -1, s(i2) = +1.  The diagonal is minus the row sum (A 1 = 0).
+template <int EC>
+__global__ void k_assemble(const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB,
+                           const V4<double>* __restrict__ GT, const int2* __restrict__ edges,
+                           const int* __restrict__ inc_off, const int* __restrict__ inc,
+                           const double* __restrict__ edge_out, int nV, double half_expo,
+                           double* __restrict__ A) {
+  const int w_ = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v_ = blockIdx.y * blockDim.y + threadIdx.y;
+  if (v_ >= nV || w_ >= nV) return;
+  if (v_ == w_) return;
+  double acc = 0.0;
+  for (int kv = inc_off[v_]; kv < inc_off[v_ + 1]; ++kv) {
+    const int I = inc[kv] >> 1;
+    const double sv = (inc[kv] & 1) ? 1.0 : -1.0;
+    const int2 ei = edges[I];
+    const V4<double> ia = GA[I], ib = GB[I], ti = GT[I];
+    for (int kw = inc_off[w_]; kw < inc_off[w_ + 1]; ++kw) {
+      const int J = inc[kw] >> 1;
+      const double sw = (inc[kw] & 1) ? 1.0 : -1.0;
+      const int2 ej = edges[J];
+      if (I == J) {
+        // v and w are the two ends of edge I
+        const double* o = edge_out + 8 * (size_t)I;  // (Wq, P0) stored at slots 0, 1
+        acc += -o[0] / (2.0 * ia.w) + ia.w * o[1] / 16.0;
+        continue;
+      }
+      if (ei.x == ej.x || ei.x == ej.y || ei.y == ej.x || ei.y == ej.y) continue;
+      const V4<double> ja = GA[J], jb = GB[J], tj = GT[J];
+      double rho = 0.0, rho0 = 0.0;
+      const V4<double>* P[2] = {&ia, &ib};
+      const V4<double>* Q[2] = {&ja, &jb};
+      for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) {
+          const double dx = P[x]->x - Q[y]->x, dy = P[x]->y - Q[y]->y, dz = P[x]->z - Q[y]->z;
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          const double rs = f_rsq<double>(r2), ri = rs * rs;
+          const double p = pow_sigma<EC, double>(r2, rs, ri, half_expo);
+          const double cI = cross_norm2<double>(ti.x, ti.y, ti.z, dx, dy, dz);
+          const double cJ = cross_norm2<double>(tj.x, tj.y, tj.z, dx, dy, dz);
+          rho += p;
+          rho0 += p * (cI + cJ) * ri * ri;
+        }
+      const double wIJ = 0.25 * ia.w * ja.w * rho;
+      const double w0s = 0.25 * ia.w * ja.w * rho0;
+      const double tt = ti.x * tj.x + ti.y * tj.y + ti.z * tj.z;
+      acc += -2.0 * sv * sw * wIJ * tt / (ia.w * ja.w) - 0.25 * w0s;
+    }
+  }
+  A[(size_t)v_ * nV + w_] = acc;
+}
+
+__global__ void k_diag_rowsum(double* __restrict__ A, int nV) {
+  __shared__ double sm[256];
+  const int v = blockIdx.x;
+  double s = 0.0;
+  for (int w = threadIdx.x; w < nV; w += 256)
+    if (w != v) s += A[(size_t)v * nV + w];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) sm[threadIdx.x] += sm[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) A[(size_t)v * nV + v] = -sm[0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+rc_status launch_geometry(const Curve& c, const double* gamma, rc_dtype prec, hipStream_t s) {
+  dim3 g(cdiv(c.nE, 256)), b(256);
+  if (prec == RC_F32)
+    hipLaunchKernelGGL(k_geometry<float>, g, b, 0, s, gamma, c.edges, c.nE, c.gf.a, c.gf.b, c.gf.t);
+  // the FP64 copy is always kept: the finalize kernels read l_I and T_I from it
+  hipLaunchKernelGGL(k_geometry<double>, g, b, 0, s, gamma, c.edges, c.nE, c.gd.a, c.gd.b, c.gd.t);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+template <typename R, int EC, bool GRAD>
+static void run_tpe(const Curve& c, const EdgeGeom<R>& g, double alpha, double beta, hipStream_t s) {
+  dim3 grid(cdiv(c.nE, kTile), c.nchunk);
+  if (std::is_same<R, float>::value && c.chain) {
+    hipLaunchKernelGGL((k_tpe_pairs<R, EC, GRAD, true>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, c.cinfo,
+                       c.nE, c.src_per_chunk, R(0.5 * alpha), R(0.5 * beta), R(beta), c.part);
+    hipLaunchKernelGGL((k_tpe_band<EC, GRAD>), dim3(cdiv(c.nE, 64)), dim3(64), 0, s, c.gd.a, c.gd.b, c.gd.t,
+                       c.edges, c.cinfo, c.chain_edge, c.nE, 0.5 * alpha, 0.5 * beta, beta, c.nchunk, c.part);
+  } else {
+    hipLaunchKernelGGL((k_tpe_pairs<R, EC, GRAD, false>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges,
+                       c.cinfo, c.nE, c.src_per_chunk, R(0.5 * alpha), R(0.5 * beta), R(beta), c.part);
+  }
+}
+
+template <typename R, bool GRAD>
+static void dispatch_tpe(const Curve& c, const EdgeGeom<R>& g, double alpha, double beta, hipStream_t s) {
+  switch (exp_case(alpha, beta)) {
+    case kA2B4: run_tpe<R, kA2B4, GRAD>(c, g, alpha, beta, s); break;
+    case kA2B45: run_tpe<R, kA2B45, GRAD>(c, g, alpha, beta, s); break;
+    case kA3B6: run_tpe<R, kA3B6, GRAD>(c, g, alpha, beta, s); break;
+    default: run_tpe<R, kGeneral, GRAD>(c, g, alpha, beta, s); break;
+  }
+}
+
+rc_status launch_tpe(const Curve& c, double alpha, double beta, rc_dtype prec, bool grad,
+                     double* energy, double* dE, hipStream_t s) {
+  if (prec == RC_F32) {
+    if (grad) dispatch_tpe<float, true>(c, c.gf, alpha, beta, s);
+    else dispatch_tpe<float, false>(c, c.gf, alpha, beta, s);
+  } else {
+    if (grad) dispatch_tpe<double, true>(c, c.gd, alpha, beta, s);
+    else dispatch_tpe<double, false>(c, c.gd, alpha, beta, s);
+  }
+  RC_HIP(hipGetLastError());
+  const int nparts = c.nchunk + ((prec == RC_F32 && c.chain) ? 1 : 0);
+  hipLaunchKernelGGL(k_tpe_finalize, dim3(cdiv(c.nE, 256)), dim3(256), 0, s, c.part, nparts, c.nE,
+                     grad ? 1 : 0, (const double*)c.gd.a, (const double*)c.gd.t, c.edge_out);
+  if (grad && dE)
+    hipLaunchKernelGGL(k_gather_vertex, dim3(cdiv(c.nV, 256)), dim3(256), 0, s, c.edge_out, c.inc_off,
+                       c.inc, c.nV, dE);
+  if (energy) sum_edge_slot(c, 0, energy, s);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+template <typename R, int EC>
+static void run_sob(const Curve& c, const EdgeGeom<R>& g, V4<R>* const* rhs, double half_expo, hipStream_t s) {
+  dim3 grid(cdiv(c.nE, kTile), c.nchunk);
+  hipLaunchKernelGGL((k_sob_pairs<R, EC>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, rhs[0], rhs[1],
+                     c.nE, c.src_per_chunk, R(half_expo), c.part);
+}
+
+template <typename R>
+static void dispatch_sob(const Curve& c, const EdgeGeom<R>& g, V4<R>* const* rhs, double alpha, double beta,
+                         hipStream_t s) {
+  const double sigma = (beta - 1.0) / alpha - 1.0;
+  const double half_expo = 0.5 * (2.0 * sigma + 1.0);
+  switch (exp_case(alpha, beta)) {
+    case kA2B4: run_sob<R, kA2B4>(c, g, rhs, half_expo, s); break;
+    case kA2B45: run_sob<R, kA2B45>(c, g, rhs, half_expo, s); break;
+    default: run_sob<R, kGeneral>(c, g, rhs, half_expo, s); break;
+  }
+}
+
+rc_status launch_sobolev(const Curve& c, double alpha, double beta, rc_dtype prec, const double* X,
+                         double* Y, double* diag, hipStream_t s) {
+  dim3 g1(cdiv(c.nE, 256)), b1(256);
+  if (prec == RC_F32) {
+    hipLaunchKernelGGL(k_edge_rhs<float>, g1, b1, 0, s, X, c.edges, c.nE, c.rhs_f[0], c.rhs_f[1]);
+    dispatch_sob<float>(c, c.gf, c.rhs_f, alpha, beta, s);
+  } else {
+    hipLaunchKernelGGL(k_edge_rhs<double>, g1, b1, 0, s, X, c.edges, c.nE, c.rhs_d[0], c.rhs_d[1]);
+    dispatch_sob<double>(c, c.gd, c.rhs_d, alpha, beta, s);
+  }
+  RC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_edge_length<double>, g1, b1, 0, s, c.gd.a, c.nE, c.edge_out);
+  hipLaunchKernelGGL(k_sob_finalize, g1, b1, 0, s, c.part, c.nchunk, c.nE, X, c.edges, c.edge_out);
+  hipLaunchKernelGGL(k_gather_sob, dim3(cdiv(c.nV, 256)), b1, 0, s, c.edge_out, c.inc_off, c.inc, c.nV, Y,
+                     diag);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+template <typename R>
+static void dispatch_mid(const Curve& c, const EdgeGeom<R>& g, double alpha, double beta, hipStream_t s) {
+  dim3 grid(cdiv(c.nE, kTile), c.nchunk);
+#define RC_MID(EC)                                                                                   \
+  hipLaunchKernelGGL((k_mid_pairs<R, EC>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, c.nE,     \
+                     c.src_per_chunk, R(0.5 * alpha), R(0.5 * beta), R(beta), c.part)
+  switch (exp_case(alpha, beta)) {
+    case kA2B4: RC_MID(kA2B4); break;
+    case kA2B45: RC_MID(kA2B45); break;
+    case kA3B6: RC_MID(kA3B6); break;
+    default: RC_MID(kGeneral); break;
+  }
+#undef RC_MID
+}
+
+rc_status launch_midpoint(const Curve& c, double alpha, double beta, rc_dtype prec, double* energy,
+                          double* dE, hipStream_t s) {
+  if (prec == RC_F32) dispatch_mid<float>(c, c.gf, alpha, beta, s);
+  else dispatch_mid<double>(c, c.gd, alpha, beta, s);
+  RC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_mid_finalize, dim3(cdiv(c.nE, 256)), dim3(256), 0, s, c.part, c.nchunk, c.nE,
+                     (const double*)c.gd.a, (const double*)c.gd.t, c.edge_out);
+  if (dE)
+    hipLaunchKernelGGL(k_gather_vertex, dim3(cdiv(c.nV, 256)), dim3(256), 0, s, c.edge_out, c.inc_off,
+                       c.inc, c.nV, dE);
+  if (energy) sum_edge_slot(c, 0, energy, s);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+// Per-edge (Wq, P0) of the operator kernel, stored in edge_out slots 0 and 1.
+__global__ void k_pick_wq_p0(const double* __restrict__ part, int nchunk, int nE, double* __restrict__ edge_out) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nE) return;
+  double wq = 0.0, p0 = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+    wq += part[((size_t)c * kSobSlots + 0) * nE + I];
+    p0 += part[((size_t)c * kSobSlots + 4) * nE + I];
+  }
+  edge_out[8 * (size_t)I] = wq;
+  edge_out[8 * (size_t)I + 1] = p0;
+}
+
+rc_status launch_assemble_dense(const Curve& c, double alpha, double beta, double* A, hipStream_t s) {
+  if (!c.chain) {
+    set_error("dense assembly needs every vertex to have degree <= 2");
+    return RC_ERR_UNSUPPORTED;
+  }
+  // the operator kernel's per-edge sums Wq and P0 do not depend on the input vector
+  dim3 g1(cdiv(c.nE, 256)), b1(256);
+  RC_HIP(hipMemsetAsync(c.rhs_d[0], 0, sizeof(V4<double>) * c.nE, s));
+  RC_HIP(hipMemsetAsync(c.rhs_d[1], 0, sizeof(V4<double>) * c.nE, s));
+  dispatch_sob<double>(c, c.gd, c.rhs_d, alpha, beta, s);
+  hipLaunchKernelGGL(k_pick_wq_p0, g1, b1, 0, s, c.part, c.nchunk, c.nE, c.edge_out);
+  const double sigma = (beta - 1.0) / alpha - 1.0;
+  const double half_expo = 0.5 * (2.0 * sigma + 1.0);
+  dim3 b2(16, 16), g2(cdiv(c.nV, 16), cdiv(c.nV, 16));
+  switch (exp_case(alpha, beta)) {
+    case kA2B4:
+      hipLaunchKernelGGL(k_assemble<kA2B4>, g2, b2, 0, s, c.gd.a, c.gd.b, c.gd.t, c.edges, c.inc_off, c.inc,
+                         c.edge_out, c.nV, half_expo, A);
+      break;
+    case kA2B45:
+      hipLaunchKernelGGL(k_assemble<kA2B45>, g2, b2, 0, s, c.gd.a, c.gd.b, c.gd.t, c.edges, c.inc_off, c.inc,
+                         c.edge_out, c.nV, half_expo, A);
+      break;
+    default:
+      hipLaunchKernelGGL(k_assemble<kGeneral>, g2, b2, 0, s, c.gd.a, c.gd.b, c.gd.t, c.edges, c.inc_off,
+                         c.inc, c.edge_out, c.nV, half_expo, A);
+      break;
+  }
+  hipLaunchKernelGGL(k_diag_rowsum, dim3(c.nV), dim3(256), 0, s, A, c.nV);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+}  // namespace rc

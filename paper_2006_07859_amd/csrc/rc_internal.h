@@ -1,0 +1,144 @@
+// Internal declarations of librcurves: device data layout, the curve record
+// shared by the finest level and the multigrid levels, and the launchers
+// implemented in the kernel sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rcurves.h"
+
+namespace rc {
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+
+#define RC_HIP(call)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      ::rc::set_error(std::string(#call " failed: ") + hipGetErrorString(e_)); \
+      return RC_ERR_HIP;                                                      \
+    }                                                                         \
+  } while (0)
+
+#define RC_TRY(expr)                     \
+  do {                                   \
+    rc_status s_ = (expr);               \
+    if (s_ != RC_OK) return s_;          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// data layout
+// ---------------------------------------------------------------------------
+// Per-edge geometry in the pair kernels' precision R, structure of arrays of
+// 4-vectors so that one source edge is three aligned 16/32-byte loads:
+//   a[I] = (x_i1, l_I)   b[I] = (x_i2, 0)   t[I] = (T_I, 0)
+// plus the endpoint indices ids[I] = (i1, i2).
+template <typename R>
+struct __align__(4 * sizeof(R)) V4 {
+  R x, y, z, w;
+};
+
+template <typename R>
+struct EdgeGeom {
+  V4<R>* a = nullptr;
+  V4<R>* b = nullptr;
+  V4<R>* t = nullptr;
+};
+
+// Partial sums written by the pair kernels: [chunk][slot][edge] doubles.
+constexpr int kTile = 256;        // threads (= target edges) per pair block
+constexpr int kSub = 64;          // sources folded into FP64 accumulators at a time
+constexpr int kTpeSlots = 14;     // energy + differential accumulators
+constexpr int kSobSlots = 8;      // operator accumulators
+constexpr int kMidSlots = 8;      // midpoint energy + differential accumulators
+
+// Exponent cases compiled as specialisations; anything else takes the
+// general exp2/log2 path.
+enum ExpCase : int { kGeneral = 0, kA2B4 = 1, kA2B45 = 2, kA3B6 = 3 };
+ExpCase exp_case(double alpha, double beta);
+
+// Components of a graph whose vertices have degree <= 2: loops and open paths.
+struct Chain {
+  std::vector<int> verts;  // v_0 .. (loop: m vertices, path: m+1 vertices)
+  std::vector<int> edges;  // e_k joins verts[k] and verts[k+1 (mod m for loops)]
+  bool loop = false;
+};
+struct Curve;
+std::vector<Chain> chains_of(const Curve& c);
+
+// Pairs of edges at most kBand apart along a chain are evaluated in FP64 by
+// the near-band kernel when the pair kernels run in FP32 (see k_pairs.hip).
+constexpr int kBand = 32;
+
+// A curve network on the device (the finest level, or a multigrid level).
+struct Curve {
+  int nV = 0, nE = 0;
+  std::vector<int> h_edges;        // [nE][2]
+  int2* edges = nullptr;           // device copy
+  int* inc_off = nullptr;          // [nV+1] CSR: vertex -> incident (edge, endpoint)
+  int* inc = nullptr;              // entries 2*edge + a (a = 0 for i1, 1 for i2)
+  std::vector<int> h_inc_off, h_inc;
+  bool chain = false;              // every vertex has degree <= 2
+  int max_degree = 0;
+
+  EdgeGeom<float> gf;
+  EdgeGeom<double> gd;
+  V4<float>* rhs_f[2] = {nullptr, nullptr};   // per-edge operator inputs (s_J, ubar_J)
+  V4<double>* rhs_d[2] = {nullptr, nullptr};
+
+  int4* cinfo = nullptr;           // per edge (chain start, position, chain length, is loop); chain graphs only
+  int* chain_edge = nullptr;       // edges in chain order (cinfo.x + position -> edge)
+
+  int nchunk = 1, src_per_chunk = 0;
+  double* part = nullptr;          // pair-kernel partials, sized for the largest slot count
+  double* edge_out = nullptr;      // per-edge finalised values [nE][8]
+  double* red = nullptr;           // reduction scratch
+  int red_blocks = 0;
+
+  rc_status init(int nV_, int nE_, const int* edges_h);
+  void release();
+};
+
+// ---------------------------------------------------------------------------
+// launchers (k_pairs.hip)
+// ---------------------------------------------------------------------------
+// Edge geometry from the FP64 state, rounded to the kernel precision.
+rc_status launch_geometry(const Curve& c, const double* gamma, rc_dtype prec, hipStream_t s);
+// Energy (and differential): writes energy[0] and, when dE != nullptr, dE[nV][3].
+rc_status launch_tpe(const Curve& c, double alpha, double beta, rc_dtype prec, bool grad,
+                     double* energy, double* dE, hipStream_t s);
+// Y = Abar X (matrix-free); when diag != nullptr also writes diag(A).
+rc_status launch_sobolev(const Curve& c, double alpha, double beta, rc_dtype prec,
+                         const double* X, double* Y, double* diag, hipStream_t s);
+// Exact edge-midpoint energy and differential.
+rc_status launch_midpoint(const Curve& c, double alpha, double beta, rc_dtype prec,
+                          double* energy, double* dE, hipStream_t s);
+// Dense FP64 A (row-major nV x nV); needs degree <= 2.
+rc_status launch_assemble_dense(const Curve& c, double alpha, double beta, double* A,
+                                hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// dense and vector helpers (k_linalg.hip)
+// ---------------------------------------------------------------------------
+// All vectors are double; n counts doubles.
+void vec_axpby(double a, const double* x, double b, double* y, int n, hipStream_t s);  // y = a x + b y
+void vec_copy(const double* x, double* y, int n, hipStream_t s);
+void vec_scale_diag_inv(const double* r, const double* d, double* z, int nV, hipStream_t s); // z = r / d (3 comps)
+// result[0] = x . y (deterministic two-pass reduction), on device
+void vec_dot(const double* x, const double* y, int n, double* scratch, double* result, hipStream_t s);
+// Dense Cholesky factorisation in place (lower), n x n row-major; info[0] = 0 on success.
+void dense_cholesky(double* A, int n, int* info, hipStream_t s);
+// Solve L L^T X = B in place, B is n x m row-major.
+void dense_chol_solve(const double* L, double* B, int n, int m, hipStream_t s);
+// C = A B (+ beta C): small dense FP64 GEMM, row-major, all device.
+void dense_gemm(const double* A, const double* B, double* C, int m, int n, int k, double beta,
+                bool transA, hipStream_t s);
+
+}  // namespace rc

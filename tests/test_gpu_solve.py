@@ -1,0 +1,151 @@
+"""GPU parity of constraints, projection, projected Sobolev gradient and step.
+
+Compared with the FP64 oracle's dense saddle solves (eqs.
+GradientSaddlePointProblem, ConstraintSaddlePointProblem) and its backtracking
+step (Sec. 4.4).  The projected gradient is unique when A is definite on
+null(C), so the solvers must agree with the oracle's solution.
+"""
+
+import numpy as np
+import pytest
+
+import gen
+from oracle import constraints as cons
+from oracle import solve, sobolev, tpe
+from tests.gpu_util import banner, dev, host, relnorm, zeros
+
+pytestmark = pytest.mark.gpu
+
+BARY, TOTAL, EDGE = 1, 2, 4
+
+
+def make(lib, g, e, a, b, dtype, mask):
+    from paper_2006_07859_amd import Context
+
+    ctx = Context(len(g), e, a, b, dtype)
+    ctx.rc_set_constraints(mask, dev(g))
+    return ctx
+
+
+def oracle_system(g, e, a, b, mask):
+    refs = cons.reference_values(g, e)
+    E, dE = tpe.differential(g, e, a, b)
+    A = sum(sobolev.assemble(g, e, a, b))
+    phi, C = cons.evaluate(g, e, mask, *refs)
+    return refs, E, dE, A, phi, C
+
+
+@pytest.mark.parametrize("mask", [BARY, BARY | EDGE, BARY | TOTAL, EDGE])
+def test_constraint_values_and_projector(lib, mask):
+    from paper_2006_07859_amd import RC_F64
+
+    banner(f"constraints mask={mask}")
+    g, e = gen.trefoil(150, seed=2)
+    ctx = make(lib, g, e, 2.0, 4.0, RC_F64, mask)
+    refs = cons.reference_values(g, e)
+    # values at a perturbed curve
+    gp = g + 0.01 * np.random.default_rng(0).normal(size=g.shape)
+    phi_ref, C = cons.evaluate(gp, e, mask, *refs)
+    phi = zeros(ctx.rc_constraint_count())
+    ctx.rc_constraint_values(dev(gp), phi)
+    assert np.abs(host(phi) - phi_ref).max() < 1e-12 * (np.abs(phi_ref).max() + 1)
+    # projector P = I - C^T (C C^T)^-1 C at gp
+    X = np.random.default_rng(1).normal(size=g.shape)
+    x = X.ravel()
+    ref = x - C.T @ np.linalg.solve(C @ C.T, C @ x)
+    Y = zeros(len(g), 3)
+    ctx.rc_project(dev(gp), dev(X), Y)
+    assert relnorm(host(Y).ravel(), ref) < 1e-11
+    assert np.abs(C @ host(Y).ravel()).max() < 1e-10 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("mask", [BARY, BARY | EDGE])
+def test_dense_gradient_c1(lib, mask):
+    from paper_2006_07859_amd import RC_F64, RC_SOLVE_DENSE, default_solve_opts
+
+    banner(f"dense projected gradient trefoil256 mask={mask}")
+    g, e = gen.trefoil(256, seed=0)
+    refs, E, dE, A, phi, C = oracle_system(g, e, 2.0, 4.0, mask)
+    g_ref, _ = solve.projected_gradient(A, C, dE)
+    ctx = make(lib, g, e, 2.0, 4.0, RC_F64, mask)
+    out = zeros(256, 3)
+    ctx.rc_sobolev_gradient(dev(g), dev(dE), out, default_solve_opts(solver=RC_SOLVE_DENSE))
+    assert relnorm(host(out), g_ref) < 1e-8
+
+
+def test_pcg_jacobi_small(lib):
+    from paper_2006_07859_amd import RC_F64, RC_SOLVE_PCG_JACOBI, default_solve_opts
+
+    banner("PCG jacobi f64 trefoil96")
+    g, e = gen.trefoil(96, seed=4)
+    refs, E, dE, A, phi, C = oracle_system(g, e, 2.0, 4.0, BARY | EDGE)
+    g_ref, _ = solve.projected_gradient(A, C, dE)
+    ctx = make(lib, g, e, 2.0, 4.0, RC_F64, BARY | EDGE)
+    out = zeros(len(g), 3)
+    st = ctx.rc_sobolev_gradient(dev(g), dev(dE), out,
+                                 default_solve_opts(solver=RC_SOLVE_PCG_JACOBI, tol=1e-11, max_iter=4000))
+    assert st["residual"] < 1e-11
+    assert relnorm(host(out), g_ref) < 1e-7
+
+
+@pytest.mark.parametrize("mask", [BARY, BARY | EDGE])
+def test_pcg_multigrid(lib, mask):
+    from paper_2006_07859_amd import RC_F32, RC_SOLVE_PCG_MG, default_solve_opts
+
+    n = 2048
+    banner(f"PCG multigrid f32 fourier{n} mask={mask}")
+    g, e, _ = gen.fourier_knot(n, seed=1)
+    g = gen.round_to_f32(g)
+    refs, E, dE, A, phi, C = oracle_system(g, e, 2.0, 4.5, mask)
+    g_ref, _ = solve.projected_gradient(A, C, dE)
+    ctx = make(lib, g, e, 2.0, 4.5, RC_F32, mask)
+    out = zeros(n, 3)
+    # FP64 operator inside PCG: the solution is certified by the FP64 residual
+    st = ctx.rc_sobolev_gradient(dev(g), dev(dE), out,
+                                 default_solve_opts(solver=RC_SOLVE_PCG_MG, tol=1e-9, op_f64=1,
+                                                    mg_min_vertices=256))
+    assert st["iterations"] < 200
+    assert relnorm(host(out), g_ref) < 1e-6
+    # FP32 operator, FP64 residual replacement: 1e-6 residual
+    st = ctx.rc_sobolev_gradient(dev(g), dev(dE), out,
+                                 default_solve_opts(solver=RC_SOLVE_PCG_MG, tol=1e-6, mg_min_vertices=256))
+    Ab = np.kron(A, np.eye(3))
+    err = host(out).ravel() - g_ref.ravel()
+    assert np.sqrt(err @ Ab @ err) / np.sqrt(g_ref.ravel() @ Ab @ g_ref.ravel()) < 1e-4
+
+
+def test_step_dense_matches_oracle(lib):
+    from paper_2006_07859_amd import RC_F64, RC_SOLVE_DENSE, default_solve_opts
+
+    banner("step dense trefoil256 barycenter")
+    g, e = gen.trefoil(256, seed=0)
+    refs = cons.reference_values(g, e)
+    new_ref, info = solve.step(g, e, 2.0, 4.0, BARY, refs)
+    ctx = make(lib, g, e, 2.0, 4.0, RC_F64, BARY)
+    gam = dev(g)
+    st = ctx.rc_step(gam, so=default_solve_opts(solver=RC_SOLVE_DENSE))
+    assert st["energy"] == pytest.approx(info["E0"], rel=1e-12)
+    assert st["tau"] == info["tau"]
+    assert st["energy_new"] == pytest.approx(info["E1"], rel=1e-10)
+    assert relnorm(host(gam) - g, new_ref - g) < 1e-7
+
+
+def test_step_multigrid_edge_lengths(lib):
+    from paper_2006_07859_amd import RC_F32, RC_SOLVE_PCG_MG, default_solve_opts
+
+    n = 1024
+    banner(f"step multigrid f32 fourier{n} barycenter+edge lengths")
+    g, e, _ = gen.fourier_knot(n, seed=2)
+    g = gen.round_to_f32(g)
+    ctx = make(lib, g, e, 2.0, 4.5, RC_F32, BARY | EDGE)
+    gam = dev(g)
+    E0 = tpe.energy(g, e, 2.0, 4.5)
+    st = ctx.rc_step(gam, so=default_solve_opts(solver=RC_SOLVE_PCG_MG, mg_min_vertices=256))
+    new = host(gam)
+    E1 = tpe.energy(new, e, 2.0, 4.5)
+    assert st["tau"] > 0 and E1 < E0
+    assert st["energy_new"] == pytest.approx(E1, rel=1e-5)
+    refs = cons.reference_values(g, e)
+    phi, _ = cons.evaluate(new, e, BARY | EDGE, *refs, jacobian=False)
+    ell, _, _ = tpe.edge_geometry(g, e)
+    assert np.abs(phi[3:]).max() < 1e-8 * ell.mean()
