@@ -100,6 +100,9 @@ typedef struct {
   int32_t proj_iters;    /* projection iterations at the accepted step */
   int32_t status;        /* rc_status of the last call */
   int32_t pad;
+  double t_eval_ms;      /* rc_step: energy + differential phase (HIP events) */
+  double t_solve_ms;     /* rc_step: constraint/multigrid setup + gradient solve */
+  double t_search_ms;    /* rc_step: line search with projection */
 } rc_stats;
 
 /* Default option values. */
@@ -203,6 +206,15 @@ rc_status rc_bh_differential(rc_ctx* ctx, const double* gamma, double theta, int
 /* Exact edge-midpoint energy and differential (the theta -> 0 limit of
  * rc_bh_differential), in the context's dtype. */
 rc_status rc_midpoint_differential(rc_ctx* ctx, const double* gamma, double* energy, double* dE);
+
+/* Kernel timing with HIP events on the context's stream.  rc_profile_enable
+ * clears earlier records and, when enable != 0, brackets every launch of the
+ * FP32/FP64 pair kernels with a pair of events.  rc_profile_read synchronises
+ * the stream and returns the summed duration (ms) and the launch count of
+ * which = 0: the energy + differential pair kernel, 1: the FP32 operator pair
+ * kernel on the finest level (coarse multigrid levels are not timed). */
+rc_status rc_profile_enable(rc_ctx* ctx, int32_t enable);
+rc_status rc_profile_read(rc_ctx* ctx, int32_t which, double* total_ms, int32_t* launches);
 
 #ifdef __cplusplus
 }

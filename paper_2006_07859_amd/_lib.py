@@ -30,7 +30,8 @@ EXPORTED = [
     "rc_default_solve_opts", "rc_default_ls_opts", "rc_last_error", "rc_create", "rc_destroy", "rc_energy",
     "rc_differential", "rc_sobolev_apply", "rc_sobolev_apply_prec", "rc_sobolev_diag", "rc_assemble_dense",
     "rc_set_constraints", "rc_constraint_values", "rc_constraint_count", "rc_project", "rc_sobolev_gradient",
-    "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_midpoint_differential",
+    "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_midpoint_differential", "rc_profile_enable",
+    "rc_profile_read",
 ]
 
 
@@ -55,7 +56,8 @@ class Stats(C.Structure):
     _fields_ = [("energy", C.c_double), ("energy_new", C.c_double), ("grad_norm", C.c_double),
                 ("residual", C.c_double), ("tau", C.c_double), ("iterations", C.c_int32),
                 ("proj_solve_iterations", C.c_int32), ("backtracks", C.c_int32), ("proj_iters", C.c_int32),
-                ("status", C.c_int32), ("pad", C.c_int32)]
+                ("status", C.c_int32), ("pad", C.c_int32), ("t_eval_ms", C.c_double), ("t_solve_ms", C.c_double),
+                ("t_search_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
@@ -95,6 +97,8 @@ def load():
         "rc_step": (I32, [P, P, C.POINTER(SolveOpts), C.POINTER(LsOpts), C.POINTER(Stats)]),
         "rc_bh_differential": (I32, [P, P, D, I32, P, P]),
         "rc_midpoint_differential": (I32, [P, P, P, P]),
+        "rc_profile_enable": (I32, [P, I32]),
+        "rc_profile_read": (I32, [P, I32, C.POINTER(D), C.POINTER(I32)]),
     }
     for name, (res, args) in sig.items():
         if not hasattr(lib, name):
@@ -250,3 +254,11 @@ class Context:
     def rc_midpoint_differential(self, gamma, energy, dE):
         _check(load().rc_midpoint_differential(self.h, self._v(gamma, "gamma"),
                                                _ptr(energy, (1,), self._f64, "energy"), self._v(dE, "dE")))
+
+    def rc_profile_enable(self, enable=True):
+        _check(load().rc_profile_enable(self.h, 1 if enable else 0))
+
+    def rc_profile_read(self, which):
+        ms, n = C.c_double(0.0), C.c_int32(0)
+        _check(load().rc_profile_read(self.h, int(which), C.byref(ms), C.byref(n)))
+        return ms.value, n.value

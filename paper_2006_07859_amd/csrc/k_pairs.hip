@@ -751,14 +751,19 @@ rc_status launch_geometry(const Curve& c, const double* gamma, rc_dtype prec, hi
 template <typename R, int EC, bool GRAD>
 static void run_tpe(const Curve& c, const EdgeGeom<R>& g, double alpha, double beta, hipStream_t s) {
   dim3 grid(cdiv(c.nE, kTile), c.nchunk);
+  const bool timed = GRAD && c.timer && c.timer->on;
   if (std::is_same<R, float>::value && c.chain) {
+    if (timed) c.timer->mark(c.timer->tpe, s);
     hipLaunchKernelGGL((k_tpe_pairs<R, EC, GRAD, true>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, c.cinfo,
                        c.nE, c.src_per_chunk, R(0.5 * alpha), R(0.5 * beta), R(beta), c.part);
+    if (timed) c.timer->mark(c.timer->tpe, s);
     hipLaunchKernelGGL((k_tpe_band<EC, GRAD>), dim3(cdiv(c.nE, 64)), dim3(64), 0, s, c.gd.a, c.gd.b, c.gd.t,
                        c.edges, c.cinfo, c.chain_edge, c.nE, 0.5 * alpha, 0.5 * beta, beta, c.nchunk, c.part);
   } else {
+    if (timed) c.timer->mark(c.timer->tpe, s);
     hipLaunchKernelGGL((k_tpe_pairs<R, EC, GRAD, false>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges,
                        c.cinfo, c.nE, c.src_per_chunk, R(0.5 * alpha), R(0.5 * beta), R(beta), c.part);
+    if (timed) c.timer->mark(c.timer->tpe, s);
   }
 }
 
@@ -796,8 +801,11 @@ rc_status launch_tpe(const Curve& c, double alpha, double beta, rc_dtype prec, b
 template <typename R, int EC>
 static void run_sob(const Curve& c, const EdgeGeom<R>& g, V4<R>* const* rhs, double half_expo, hipStream_t s) {
   dim3 grid(cdiv(c.nE, kTile), c.nchunk);
+  const bool timed = std::is_same<R, float>::value && c.timer && c.timer->on;
+  if (timed) c.timer->mark(c.timer->sob, s);
   hipLaunchKernelGGL((k_sob_pairs<R, EC>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, rhs[0], rhs[1],
                      c.nE, c.src_per_chunk, R(half_expo), c.part);
+  if (timed) c.timer->mark(c.timer->sob, s);
 }
 
 template <typename R>

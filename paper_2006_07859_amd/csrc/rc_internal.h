@@ -77,6 +77,25 @@ std::vector<Chain> chains_of(const Curve& c);
 // the near-band kernel when the pair kernels run in FP32 (see k_pairs.hip).
 constexpr int kBand = 32;
 
+// Optional HIP-event timing of the pair kernels (enabled per context).
+struct KernelTimer {
+  bool on = false;
+  std::vector<hipEvent_t> tpe, sob;  // start/stop pairs, in launch order
+  void mark(std::vector<hipEvent_t>& v, hipStream_t s) {
+    if (!on) return;
+    hipEvent_t e;
+    hipEventCreate(&e);
+    hipEventRecord(e, s);
+    v.push_back(e);
+  }
+  void clear() {
+    for (hipEvent_t e : tpe) hipEventDestroy(e);
+    for (hipEvent_t e : sob) hipEventDestroy(e);
+    tpe.clear();
+    sob.clear();
+  }
+};
+
 // A curve network on the device (the finest level, or a multigrid level).
 struct Curve {
   int nV = 0, nE = 0;
@@ -95,6 +114,8 @@ struct Curve {
 
   int4* cinfo = nullptr;           // per edge (chain start, position, chain length, is loop); chain graphs only
   int* chain_edge = nullptr;       // edges in chain order (cinfo.x + position -> edge)
+
+  KernelTimer* timer = nullptr;    // set on the finest level when profiling is on
 
   int nchunk = 1, src_per_chunk = 0;
   double* part = nullptr;          // pair-kernel partials, sized for the largest slot count

@@ -1,0 +1,108 @@
+// Solver state of a context: constraints, dense saddle factorisation and the
+// multigrid hierarchy, each held per level (level 0 is the context's curve).
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "rc_internal.h"
+
+namespace rc {
+
+// Constraint Jacobian C of one curve, split into "path" rows (edge-length
+// rows in chain order, a block-tridiagonal C_p C_p^T) and dense "border" rows
+// (barycenter, total length, and the first edge of every loop, whose removal
+// leaves the path rows tridiagonal).  C C^T is solved through the border
+// Schur complement S = K_bb - K_pb^T K_pp^-1 K_pb.
+struct Cons {
+  uint32_t mask = 0;
+  int bary = 0, total = 0, edge = 0;
+  int nb = 0, np = 0, ncut = 0, k = 0;  // border rows, path rows, cut edges, all rows
+  double total0 = 0.0;
+  std::vector<int> h_path_edge, h_path_prev, h_cut_edge, h_edge_path_row;
+  int *path_edge = nullptr, *path_prev = nullptr, *cut_edge = nullptr, *edge_path_row = nullptr;
+  double *x0 = nullptr, *len0 = nullptr, *ones = nullptr;
+  double *geo = nullptr, *geo_eval = nullptr, *vals = nullptr;
+  double *rows = nullptr, *ta = nullptr, *td = nullptr, *tc = nullptr;
+  double *Kpb = nullptr, *Z = nullptr, *Sinv = nullptr, *tri_scratch = nullptr;
+  double *wp = nullptr, *yp = nullptr, *wb = nullptr, *yb = nullptr, *dots = nullptr, *rhs = nullptr;
+  double* small = nullptr;
+};
+
+// Dense FP64 saddle solve on one curve: H = Abar + C^T C (Cholesky),
+// W = H^-1 C^T, S = C W.  Projected gradient with right-hand side b:
+// x = H^-1 b - W S^-1 W^T b; projection increment: x = -W S^-1 phi.
+struct Dense {
+  int nV = 0, k = 0;
+  double *A = nullptr, *Cd = nullptr, *CtC = nullptr, *H = nullptr, *W = nullptr, *S = nullptr, *Sinv = nullptr,
+         *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
+  int* info = nullptr;
+};
+
+struct Level {
+  Curve curve;
+  Cons cons;
+  int* fine_of = nullptr;  // coarse vertex -> fine vertex index
+  int2* prolong = nullptr; // fine vertex -> (coarse a, coarse b): value (x_a + x_b) / 2
+  int *restr_off = nullptr, *restr_idx = nullptr;  // coarse vertex -> fine vertices that reference it
+  double* gamma = nullptr; // the level's vertex positions [nV][3]
+};
+
+struct MGLevelState {
+  double *diag = nullptr, *x = nullptr, *b = nullptr, *r = nullptr, *d = nullptr, *t = nullptr, *pw = nullptr;
+  double lmax = 0.0;
+};
+
+}  // namespace rc
+
+struct rc_ctx {
+  int nV = 0, nE = 0;
+  double alpha = 0, beta = 0;
+  rc_dtype dtype = RC_F64;
+  hipStream_t stream = nullptr;
+  rc::Curve curve;
+  rc::Cons cons;
+  // FP64 work vectors [3 nV]
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *tmp = nullptr, *tmp2 = nullptr;
+  double *diag = nullptr, *scal = nullptr, *red = nullptr, *trial = nullptr, *zmin = nullptr, *inc = nullptr;
+  double *phi = nullptr, *dx = nullptr, *dEs = nullptr, *gs = nullptr;
+  // multigrid: levels[0] is a placeholder for the finest level (curve, cons)
+  std::vector<std::unique_ptr<rc::Level>> levels;
+  std::vector<rc::MGLevelState> mg;
+  rc::Dense coarse;  // dense saddle of the coarsest level
+  bool mg_built = false;
+  int mg_min = 0, cheb_deg = 0;
+  // dense direct path on the finest level
+  rc::Dense dense;
+  rc::KernelTimer timer;
+};
+
+namespace rc {
+
+rc_status sync(rc_ctx* c);
+rc_status fetch(rc_ctx* c, const double* dev, double* host, int n);
+bool trace_on();
+
+rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask);
+void cons_free(Cons& k);
+rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma);
+void cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double* out);
+void cons_values(rc_ctx* c, const double* gamma, double* phi);
+rc_status cons_set_targets(rc_ctx* c, const double* gamma_ref, const double* x0_h, double total_len0,
+                           const double* edge_len0);
+
+void dense_free(Dense& d);
+void mg_free(rc_ctx* c);
+
+rc_status load_geometry(rc_ctx* c, const double* gamma);
+rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o);
+rc_status solve_prepared(rc_ctx* c, const double* rhs, double* out, const rc_solve_opts& o, int* iters, double* res);
+
+struct LsResult {
+  double tau = 0.0, E1 = 0.0;
+  int backtracks = 0, proj_iters = 0, proj_solve_iters = 0;
+};
+rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, const double* g, const rc_ls_opts& ls,
+                      const rc_solve_opts& so, LsResult* out);
+
+}  // namespace rc

@@ -1,0 +1,951 @@
+// Host orchestration of the constrained Sobolev solve (paper Sec. 4.3-4.4,
+// App. B.3): constraint projection, dense saddle factorisation, projected
+// multigrid-preconditioned CG, constraint projection of trial steps and the
+// backtracking line search.
+//
+// The host drives the loops and reads back only the scalars that decide
+// control flow; every vector operation runs in the kernels of k_pairs.hip and
+// k_linalg.hip.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "k_linalg.h"
+#include "solver.h"
+
+namespace rc {
+
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+template <typename T>
+static rc_status dalloc(T** p, size_t n) {
+  *p = nullptr;
+  hipError_t e = hipMalloc((void**)p, sizeof(T) * std::max<size_t>(n, 1));
+  if (e != hipSuccess) {
+    set_error(std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    return RC_ERR_NOMEM;
+  }
+  return RC_OK;
+}
+
+template <typename T>
+static void dfree(T*& p) {
+  if (p) hipFree(p);
+  p = nullptr;
+}
+
+rc_status sync(rc_ctx* c) {
+  RC_HIP(hipStreamSynchronize(c->stream));
+  return RC_OK;
+}
+
+rc_status fetch(rc_ctx* c, const double* dev, double* host, int n) {
+  RC_HIP(hipMemcpyAsync(host, dev, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
+
+bool trace_on() {
+  static int on = -1;
+  if (on < 0) {
+    const char* v = getenv("RC_TRACE");
+    on = (v && v[0] == '1') ? 1 : 0;
+  }
+  return on == 1;
+}
+
+// Gauss-Jordan inverse with partial pivoting (small border systems).
+static bool invert_small(std::vector<double>& A, int n) {
+  std::vector<double> I(n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(A[r * n + col]) > std::fabs(A[piv * n + col])) piv = r;
+    if (!(std::fabs(A[piv * n + col]) > 0.0)) return false;
+    if (piv != col)
+      for (int j = 0; j < n; ++j) {
+        std::swap(A[col * n + j], A[piv * n + j]);
+        std::swap(I[col * n + j], I[piv * n + j]);
+      }
+    const double d = 1.0 / A[col * n + col];
+    for (int j = 0; j < n; ++j) {
+      A[col * n + j] *= d;
+      I[col * n + j] *= d;
+    }
+    for (int r = 0; r < n; ++r)
+      if (r != col) {
+        const double f = A[r * n + col];
+        if (f == 0.0) continue;
+        for (int j = 0; j < n; ++j) {
+          A[r * n + j] -= f * A[col * n + j];
+          I[r * n + j] -= f * I[col * n + j];
+        }
+      }
+  }
+  A = I;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+__global__ void k_map_rhs(const double* __restrict__ b, int bary, int total, const int* __restrict__ path_edge,
+                          int np, const int* __restrict__ cut_edge, int ncut, double* __restrict__ wp,
+                          double* __restrict__ wb, double sign) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nd = 3 * bary + total;
+  if (i < np) wp[i] = sign * b[nd + path_edge[i]];
+  if (i < nd) wb[i] = sign * b[i];
+  if (i < ncut) wb[nd + i] = sign * b[nd + cut_edge[i]];
+}
+
+__global__ void k_phi_border(const double* __restrict__ sm, int bary, int total, double total0,
+                             double* __restrict__ phi) {
+  int o = 0;
+  if (bary) {
+    phi[0] = sm[0];
+    phi[1] = sm[1];
+    phi[2] = sm[2];
+    o = 3;
+  }
+  if (total) phi[o] = total0 - sm[3];
+}
+
+__global__ void k_gather_coarse(const double* __restrict__ fine, const int* __restrict__ fine_of, int nc,
+                                double* __restrict__ coarse) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc) return;
+  int f = fine_of[i];
+  coarse[3 * i] = fine[3 * f];
+  coarse[3 * i + 1] = fine[3 * f + 1];
+  coarse[3 * i + 2] = fine[3 * f + 2];
+}
+
+// xf = J xc: fine v gets (x_a + x_b)/2 (a = b for kept vertices)
+__global__ void k_prolong(const int2* __restrict__ pr, int nf, const double* __restrict__ xc, double* __restrict__ xf) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nf) return;
+  int2 ab = pr[v];
+  for (int k = 0; k < 3; ++k) xf[3 * v + k] = 0.5 * (xc[3 * ab.x + k] + xc[3 * ab.y + k]);
+}
+
+// bc = J^T rf
+__global__ void k_restrict(const int* __restrict__ off, const int* __restrict__ idx, const int2* __restrict__ pr,
+                           int nc, const double* __restrict__ rf, double* __restrict__ bc) {
+  int cidx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cidx >= nc) return;
+  double s[3] = {0, 0, 0};
+  for (int k = off[cidx]; k < off[cidx + 1]; ++k) {
+    int v = idx[k];
+    int2 ab = pr[v];
+    double w = 0.5 * ((ab.x == cidx) + (ab.y == cidx));
+    for (int d = 0; d < 3; ++d) s[d] += w * rf[3 * v + d];
+  }
+  for (int d = 0; d < 3; ++d) bc[3 * cidx + d] = s[d];
+}
+
+__global__ void k_cheb_init(const double* __restrict__ r, const double* __restrict__ dg, double inv_theta, int nV,
+                            double* __restrict__ d) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 3 * nV) d[i] = inv_theta * r[i] / dg[i / 3];
+}
+
+__global__ void k_cheb_update(const double* __restrict__ r, const double* __restrict__ dg, double c1, double c2,
+                              int nV, double* __restrict__ d) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 3 * nV) d[i] = c1 * d[i] + c2 * r[i] / dg[i / 3];
+}
+
+__global__ void k_add_const(double* __restrict__ A, int n, double rho) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n * n) A[i] += rho;
+}
+
+__global__ void k_identity(double* __restrict__ A, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n * n) A[i] = (i / n == i % n) ? 1.0 : 0.0;
+}
+
+__global__ void k_negate(const double* __restrict__ in, double* __restrict__ out, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = -in[i];
+}
+
+__global__ void k_fill_pattern(double* __restrict__ x, int n, unsigned seed) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned h = (unsigned)i * 2654435761u ^ seed;
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  x[i] = (double)(h & 0xffffff) / 16777216.0 - 0.5;
+}
+
+// ---------------------------------------------------------------------------
+// constraints of one level
+// ---------------------------------------------------------------------------
+void cons_free(Cons& k) {
+  int* ip[] = {k.path_edge, k.path_prev, k.cut_edge, k.edge_path_row};
+  for (int* p : ip)
+    if (p) hipFree(p);
+  double* dp[] = {k.x0, k.len0, k.ones, k.geo, k.geo_eval, k.vals, k.rows, k.ta, k.td, k.tc, k.Kpb, k.Z, k.Sinv,
+                  k.tri_scratch, k.wp, k.yp, k.wb, k.yb, k.dots, k.rhs, k.small};
+  for (double* p : dp)
+    if (p) hipFree(p);
+  k = Cons();
+}
+
+rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask) {
+  (void)c;
+  cons_free(k);
+  k.mask = mask;
+  k.bary = (mask & RC_C_BARYCENTER) ? 1 : 0;
+  k.total = (mask & RC_C_TOTAL_LENGTH) ? 1 : 0;
+  k.edge = (mask & RC_C_EDGE_LENGTH) ? 1 : 0;
+  const int nV = cv.nV, nE = cv.nE;
+  k.h_edge_path_row.assign(nE, -1);
+  if (k.edge) {
+    for (const Chain& ch : chains_of(cv)) {
+      const int m = (int)ch.edges.size();
+      for (int q = 0; q < m; ++q) {
+        if (ch.loop && q == 0) {
+          k.h_cut_edge.push_back(ch.edges[0]);
+          continue;
+        }
+        k.h_edge_path_row[ch.edges[q]] = (int)k.h_path_edge.size();
+        const bool has_prev = ch.loop ? q > 1 : q > 0;
+        k.h_path_prev.push_back(has_prev ? 1 : 0);
+        k.h_path_edge.push_back(ch.edges[q]);
+      }
+    }
+  }
+  k.np = (int)k.h_path_edge.size();
+  k.ncut = (int)k.h_cut_edge.size();
+  k.nb = 3 * k.bary + k.total + k.ncut;
+  k.k = 3 * k.bary + k.total + (k.edge ? nE : 0);
+  if (k.nb > 120) {
+    set_error("too many loops for edge-length constraints (at most 120 border rows)");
+    return RC_ERR_UNSUPPORTED;
+  }
+  RC_TRY(dalloc(&k.path_edge, k.np));
+  RC_TRY(dalloc(&k.path_prev, k.np));
+  RC_TRY(dalloc(&k.cut_edge, k.ncut));
+  RC_TRY(dalloc(&k.edge_path_row, nE));
+  if (k.np) {
+    RC_HIP(hipMemcpy(k.path_edge, k.h_path_edge.data(), sizeof(int) * k.np, hipMemcpyHostToDevice));
+    RC_HIP(hipMemcpy(k.path_prev, k.h_path_prev.data(), sizeof(int) * k.np, hipMemcpyHostToDevice));
+  }
+  if (k.ncut) RC_HIP(hipMemcpy(k.cut_edge, k.h_cut_edge.data(), sizeof(int) * k.ncut, hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(k.edge_path_row, k.h_edge_path_row.data(), sizeof(int) * nE, hipMemcpyHostToDevice));
+  RC_TRY(dalloc(&k.x0, 3));
+  RC_TRY(dalloc(&k.len0, nE));
+  RC_TRY(dalloc(&k.ones, nE));
+  RC_TRY(dalloc(&k.geo, 8 * (size_t)nE));
+  RC_TRY(dalloc(&k.geo_eval, 8 * (size_t)nE));
+  RC_TRY(dalloc(&k.vals, 4 * (size_t)nE));
+  RC_TRY(dalloc(&k.rows, (size_t)std::max(k.nb, 1) * 3 * nV));
+  RC_TRY(dalloc(&k.ta, k.np));
+  RC_TRY(dalloc(&k.td, k.np));
+  RC_TRY(dalloc(&k.tc, k.np));
+  RC_TRY(dalloc(&k.Kpb, (size_t)std::max(k.nb, 1) * std::max(k.np, 1)));
+  RC_TRY(dalloc(&k.Z, (size_t)std::max(k.nb, 1) * std::max(k.np, 1)));
+  RC_TRY(dalloc(&k.Sinv, (size_t)std::max(k.nb * k.nb, 1)));
+  RC_TRY(dalloc(&k.tri_scratch, 4 * (size_t)std::max(k.np, 1)));
+  RC_TRY(dalloc(&k.wp, k.np));
+  RC_TRY(dalloc(&k.yp, k.np));
+  RC_TRY(dalloc(&k.wb, std::max(k.nb, 1)));
+  RC_TRY(dalloc(&k.yb, std::max(k.nb, 1)));
+  RC_TRY(dalloc(&k.rhs, std::max(k.nb, 1)));
+  RC_TRY(dalloc(&k.dots, (size_t)std::max(k.nb * k.nb, 4)));
+  RC_TRY(dalloc(&k.small, (size_t)std::max(k.nb * k.nb, 8)));
+  std::vector<double> ones(nE, 1.0);
+  RC_HIP(hipMemcpy(k.ones, ones.data(), sizeof(double) * nE, hipMemcpyHostToDevice));
+  RC_HIP(hipMemset(k.x0, 0, sizeof(double) * 3));
+  return RC_OK;
+}
+
+// Targets of the finest level's constraints (x0, L0, l0) from gamma_ref.
+rc_status cons_set_targets(rc_ctx* c, const double* gamma_ref, const double* x0_h, double total_len0,
+                           const double* edge_len0) {
+  Cons& k = c->cons;
+  hipStream_t s = c->stream;
+  const int nE = c->nE;
+  cons_geometry(gamma_ref, c->curve.edges, nE, k.geo_eval, s);
+  RC_HIP(hipMemsetAsync(k.x0, 0, sizeof(double) * 3, s));
+  cons_phi_edge(k.geo_eval, k.x0, nE, k.ones, k.vals, nullptr, s);
+  vec_dots(k.vals, nE, k.ones, 0, nE, 4, c->red, k.small, s);
+  double sums[4];
+  RC_TRY(fetch(c, k.small, sums, 4));
+  double x0[3] = {sums[0] / sums[3], sums[1] / sums[3], sums[2] / sums[3]};
+  if (x0_h) std::memcpy(x0, x0_h, sizeof(x0));
+  RC_HIP(hipMemcpy(k.x0, x0, sizeof(double) * 3, hipMemcpyHostToDevice));
+  k.total0 = total_len0 >= 0 ? total_len0 : sums[3];
+  if (edge_len0)
+    RC_HIP(hipMemcpyAsync(k.len0, edge_len0, sizeof(double) * nE, hipMemcpyDeviceToDevice, s));
+  else  // l0 = current lengths: column 3 of vals holds l_I
+    RC_HIP(hipMemcpyAsync(k.len0, k.vals + 3 * (size_t)nE, sizeof(double) * nE, hipMemcpyDeviceToDevice, s));
+  return sync(c);
+}
+
+// C(gamma), the tridiagonal path block and the border Schur complement.
+rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma) {
+  if (k.k == 0) return RC_OK;
+  hipStream_t s = c->stream;
+  const int nV = cv.nV, nE = cv.nE;
+  cons_geometry(gamma, cv.edges, nE, k.geo, s);
+  cons_border_rows(k.geo, cv.inc_off, cv.inc, cv.edges, k.x0, nV, k.bary, k.total, k.cut_edge, k.ncut, k.rows,
+                   k.nb, s);
+  const int nb = k.nb, np = k.np;
+  if (np > 0) cons_path_coeffs(k.geo, cv.edges, k.path_edge, k.path_prev, np, k.ta, k.td, k.tc, s);
+  if (nb > 0) {
+    for (int r = 0; r < nb; ++r)
+      vec_dots(k.rows, 3 * nV, k.rows + (size_t)r * 3 * nV, 0, 3 * nV, nb, c->red, k.dots + r * nb, s);
+    if (np > 0) {
+      cons_path_apply(k.geo, cv.edges, k.path_edge, np, k.rows, nV, nb, k.Kpb, s);
+      for (int r = 0; r < nb; ++r)
+        tridiag_solve(k.ta, k.td, k.tc, k.Kpb + (size_t)r * np, k.Z + (size_t)r * np, np, k.tri_scratch, s);
+      for (int r = 0; r < nb; ++r) vec_dots(k.Kpb, np, k.Z + (size_t)r * np, 0, np, nb, c->red, k.small + r * nb, s);
+    }
+    std::vector<double> S(nb * nb), kz(nb * nb, 0.0);
+    RC_TRY(fetch(c, k.dots, S.data(), nb * nb));
+    if (np > 0) RC_TRY(fetch(c, k.small, kz.data(), nb * nb));
+    for (int i = 0; i < nb * nb; ++i) S[i] -= kz[i];
+    if (!invert_small(S, nb)) {
+      set_error("constraint Schur complement is singular (dependent constraints?)");
+      return RC_ERR_SINGULAR;
+    }
+    RC_HIP(hipMemcpyAsync(k.Sinv, S.data(), sizeof(double) * nb * nb, hipMemcpyHostToDevice, s));
+  }
+  return sync(c);
+}
+
+// (wp, wb) -> (yp, yb) = (C C^T)^-1 w
+static void cons_solve_K(rc_ctx* c, Cons& k) {
+  hipStream_t s = c->stream;
+  if (k.np > 0) tridiag_solve(k.ta, k.td, k.tc, k.wp, k.yp, k.np, k.tri_scratch, s);
+  if (k.nb > 0) {
+    if (k.np > 0) vec_dots(k.Kpb, k.np, k.yp, 0, k.np, k.nb, c->red, k.dots, s);
+    else hipMemsetAsync(k.dots, 0, sizeof(double) * k.nb, s);
+    cons_border_solve(k.Sinv, k.wb, k.dots, k.rhs, k.nb, k.yb, s);
+    cons_sub_Zy(k.Z, k.yb, k.nb, k.np, k.yp, s);
+  }
+}
+
+// out = P in with P = I - C^T (C C^T)^-1 C (in may equal out).
+void cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double* out) {
+  hipStream_t s = c->stream;
+  const int nV = cv.nV;
+  if (k.k == 0) {
+    if (in != out) vec_copy(in, out, 3 * nV, s);
+    return;
+  }
+  cons_path_apply(k.geo, cv.edges, k.path_edge, k.np, in, nV, 1, k.wp, s);
+  if (k.nb > 0) vec_dots(k.rows, 3 * nV, in, 0, 3 * nV, k.nb, c->red, k.wb, s);
+  cons_solve_K(c, k);
+  cons_apply_CT(k.geo, cv.inc_off, cv.inc, k.edge_path_row, k.yp, k.rows, k.yb, k.nb, nV, in, out, s);
+}
+
+// z = C^T (C C^T)^-1 b for an external-order b (finest level).
+static void cons_min_norm(rc_ctx* c, const double* b, double* z) {
+  Cons& k = c->cons;
+  const int n = std::max(k.np, std::max(k.nb, 1));
+  hipLaunchKernelGGL(k_map_rhs, dim3(cdiv(n, 256)), dim3(256), 0, c->stream, b, k.bary, k.total, k.path_edge, k.np,
+                     k.cut_edge, k.ncut, k.wp, k.wb, -1.0);
+  cons_solve_K(c, k);
+  // apply_CT computes in - C^T y with in = null: -C^T y, and y = K^-1 (-b)
+  cons_apply_CT(k.geo, c->curve.inc_off, c->curve.inc, k.edge_path_row, k.yp, k.rows, k.yb, k.nb, c->nV, nullptr, z,
+                c->stream);
+}
+
+// Phi(gamma) in external order (barycenter, total length, edges).
+void cons_values(rc_ctx* c, const double* gamma, double* phi) {
+  Cons& k = c->cons;
+  hipStream_t s = c->stream;
+  const int nE = c->nE;
+  cons_geometry(gamma, c->curve.edges, nE, k.geo_eval, s);
+  const int nd = 3 * k.bary + k.total;
+  cons_phi_edge(k.geo_eval, k.x0, nE, k.len0, k.vals, k.edge ? phi + nd : nullptr, s);
+  if (nd > 0) {
+    vec_dots(k.vals, nE, k.ones, 0, nE, 4, c->red, k.small, s);
+    hipLaunchKernelGGL(k_phi_border, dim3(1), dim3(1), 0, s, k.small, k.bary, k.total, k.total0, phi);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dense saddle on one level
+// ---------------------------------------------------------------------------
+void dense_free(Dense& d) {
+  dfree(d.A);
+  dfree(d.Cd);
+  dfree(d.CtC);
+  dfree(d.H);
+  dfree(d.W);
+  dfree(d.S);
+  dfree(d.Sinv);
+  dfree(d.t1);
+  dfree(d.t2);
+  dfree(d.t3);
+  dfree(d.info);
+  d = Dense();
+}
+
+static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, const double* gamma) {
+  hipStream_t s = c->stream;
+  const int nV = cv.nV, n = 3 * nV, kk = k.k;
+  if (nV > 2048) {
+    set_error("dense solver limited to 2048 vertices");
+    return RC_ERR_UNSUPPORTED;
+  }
+  if (d.nV != nV || d.k != kk) {
+    dense_free(d);
+    d.nV = nV;
+    d.k = kk;
+    RC_TRY(dalloc(&d.A, (size_t)nV * nV));
+    RC_TRY(dalloc(&d.H, (size_t)n * n));
+    RC_TRY(dalloc(&d.CtC, (size_t)n * n));
+    RC_TRY(dalloc(&d.Cd, (size_t)std::max(kk, 1) * n));
+    RC_TRY(dalloc(&d.W, (size_t)n * std::max(kk, 1)));
+    RC_TRY(dalloc(&d.S, (size_t)std::max(kk * kk, 1)));
+    RC_TRY(dalloc(&d.Sinv, (size_t)std::max(kk * kk, 1)));
+    RC_TRY(dalloc(&d.t1, (size_t)std::max(kk, 1)));
+    RC_TRY(dalloc(&d.t2, (size_t)std::max(kk, 1)));
+    RC_TRY(dalloc(&d.t3, (size_t)n));
+    RC_TRY(dalloc(&d.info, 1));
+  }
+  RC_TRY(launch_geometry(cv, gamma, RC_F32, s));
+  RC_TRY(launch_assemble_dense(cv, c->alpha, c->beta, d.A, s));
+  if (kk > 0) {
+    // dense C in external order: border rows (barycenter, total length), then edge rows
+    const int nd = 3 * k.bary + k.total;
+    RC_HIP(hipMemsetAsync(d.Cd, 0, sizeof(double) * (size_t)kk * n, s));
+    if (nd > 0) RC_HIP(hipMemcpyAsync(d.Cd, k.rows, sizeof(double) * (size_t)nd * n, hipMemcpyDeviceToDevice, s));
+    if (k.edge) dense_C_edges(k.geo, cv.edges, cv.nE, nd, nV, d.Cd, s);
+    dense_gemm(d.Cd, d.Cd, d.CtC, n, n, kk, 0.0, true, s);
+  } else {
+    // no constraint: regularise the constant null space with rho 1 1^T per component
+    std::vector<double> Ah((size_t)nV * nV);
+    RC_HIP(hipMemcpyAsync(Ah.data(), d.A, sizeof(double) * nV * nV, hipMemcpyDeviceToHost, s));
+    RC_TRY(sync(c));
+    double tr = 0;
+    for (int i = 0; i < nV; ++i) tr += Ah[(size_t)i * nV + i];
+    hipLaunchKernelGGL(k_add_const, dim3(cdiv(nV * nV, 256)), dim3(256), 0, s, d.A, nV, tr / ((double)nV * nV));
+    RC_HIP(hipMemsetAsync(d.CtC, 0, sizeof(double) * (size_t)n * n, s));
+  }
+  dense_build_H(d.A, d.CtC, nV, d.H, s);
+  dense_cholesky(d.H, n, d.info, s);
+  int info = 0;
+  RC_HIP(hipMemcpyAsync(&info, d.info, sizeof(int), hipMemcpyDeviceToHost, s));
+  RC_TRY(sync(c));
+  if (info != 0) {
+    set_error("Cholesky of Abar + C^T C failed: Abar is not definite on null(C)");
+    return RC_ERR_SINGULAR;
+  }
+  if (kk > 0) {
+    double* Ik;
+    RC_TRY(dalloc(&Ik, (size_t)kk * kk));
+    hipLaunchKernelGGL(k_identity, dim3(cdiv(kk * kk, 256)), dim3(256), 0, s, Ik, kk);
+    dense_gemm(d.Cd, Ik, d.W, n, kk, kk, 0.0, true, s);  // W = C^T
+    dense_chol_solve(d.H, d.W, n, kk, s);                 // W = H^-1 C^T
+    dense_gemm(d.Cd, d.W, d.S, kk, kk, n, 0.0, false, s);
+    std::vector<double> S((size_t)kk * kk);
+    RC_HIP(hipMemcpyAsync(S.data(), d.S, sizeof(double) * kk * kk, hipMemcpyDeviceToHost, s));
+    RC_TRY(sync(c));
+    hipFree(Ik);
+    if (!invert_small(S, kk)) {
+      set_error("constraint Schur complement is singular");
+      return RC_ERR_SINGULAR;
+    }
+    RC_HIP(hipMemcpyAsync(d.Sinv, S.data(), sizeof(double) * kk * kk, hipMemcpyHostToDevice, s));
+  }
+  return sync(c);
+}
+
+// x = H^-1 b - W S^-1 W^T b: the saddle solution with right-hand side (b, 0).
+static void dense_solve(rc_ctx* c, Dense& d, const double* b, double* x) {
+  hipStream_t s = c->stream;
+  const int n = 3 * d.nV, k = d.k;
+  vec_copy(b, x, n, s);
+  dense_chol_solve(d.H, x, n, 1, s);
+  if (k > 0) {
+    dense_gemm(d.Cd, x, d.t1, k, 1, n, 0.0, false, s);  // C H^-1 b = W^T b
+    dense_gemm(d.Sinv, d.t1, d.t2, k, 1, k, 0.0, false, s);
+    dense_gemm(d.W, d.t2, d.t3, n, 1, k, 0.0, false, s);
+    vec_axpby(-1.0, d.t3, 1.0, x, n, s);
+  }
+}
+
+// x = -W S^-1 phi: the saddle solution with right-hand side (0, -phi).
+static void dense_increment(rc_ctx* c, Dense& d, const double* phi, double* x) {
+  hipStream_t s = c->stream;
+  const int n = 3 * d.nV, k = d.k;
+  dense_gemm(d.Sinv, phi, d.t1, k, 1, k, 0.0, false, s);
+  dense_gemm(d.W, d.t1, x, n, 1, k, 0.0, false, s);
+  vec_axpby(0.0, x, -1.0, x, n, s);
+}
+
+// ---------------------------------------------------------------------------
+// projected multigrid (App. B.3.1-B.3.3): every level carries its own
+// constraints and projector, smooths P A P with projected Chebyshev-Jacobi,
+// and the coarsest level solves its saddle problem densely.
+// ---------------------------------------------------------------------------
+static const Curve& level_curve(rc_ctx* c, int l) { return l == 0 ? c->curve : c->levels[l]->curve; }
+static Cons& level_cons(rc_ctx* c, int l) { return l == 0 ? c->cons : c->levels[l]->cons; }
+
+rc_status load_geometry(rc_ctx* c, const double* gamma) { return launch_geometry(c->curve, gamma, RC_F32, c->stream); }
+
+void mg_free(rc_ctx* c) {
+  for (auto& L : c->levels)
+    if (L) {
+      L->curve.release();
+      cons_free(L->cons);
+      dfree(L->fine_of);
+      dfree(L->prolong);
+      dfree(L->restr_off);
+      dfree(L->restr_idx);
+      dfree(L->gamma);
+    }
+  c->levels.clear();
+  for (auto& st : c->mg) {
+    dfree(st.diag);
+    dfree(st.x);
+    dfree(st.b);
+    dfree(st.r);
+    dfree(st.d);
+    dfree(st.t);
+    dfree(st.pw);
+  }
+  c->mg.clear();
+  dense_free(c->coarse);
+  c->mg_built = false;
+}
+
+static rc_status mg_build(rc_ctx* c) {
+  if (c->mg_built) return RC_OK;
+  if (!c->curve.chain) {
+    set_error("multigrid needs every vertex to have degree <= 2");
+    return RC_ERR_UNSUPPORTED;
+  }
+  mg_free(c);
+  c->levels.emplace_back(nullptr);
+  const Curve* fine = &c->curve;
+  while (fine->nV > c->mg_min) {
+    std::vector<Chain> chs = chains_of(*fine);
+    // black/white coarsening: keep even chain positions, and both ends of open paths
+    std::vector<int> coarse_id(fine->nV, -1), fine_of, cedges;
+    std::vector<int2> prolong(fine->nV, make_int2(-1, -1));
+    bool ok = true;
+    for (const Chain& ch : chs) {
+      const int m = (int)ch.verts.size();
+      if (ch.loop && m < 12) {
+        ok = false;
+        break;
+      }
+      std::vector<int> keep;
+      for (int i = 0; i < m; ++i)
+        if (i % 2 == 0 || (!ch.loop && i == m - 1)) keep.push_back(i);
+      for (int i : keep) {
+        coarse_id[ch.verts[i]] = (int)fine_of.size();
+        fine_of.push_back(ch.verts[i]);
+      }
+      const int nk = (int)keep.size();
+      for (int q = 0; q + 1 < nk || (ch.loop && q < nk); ++q) {
+        cedges.push_back(coarse_id[ch.verts[keep[q]]]);
+        cedges.push_back(coarse_id[ch.verts[keep[(q + 1) % nk]]]);
+      }
+      for (int q = 0; q < nk; ++q) {
+        const int i0 = keep[q];
+        const int i1 = (q + 1 < nk) ? keep[q + 1] : (ch.loop ? keep[0] + m : -1);
+        prolong[ch.verts[i0]] = make_int2(coarse_id[ch.verts[i0]], coarse_id[ch.verts[i0]]);
+        if (i1 < 0) continue;
+        for (int i = i0 + 1; i < i1; ++i)
+          prolong[ch.verts[i % m]] = make_int2(coarse_id[ch.verts[i0]], coarse_id[ch.verts[i1 % m]]);
+      }
+    }
+    for (int v = 0; ok && v < fine->nV; ++v)
+      if (prolong[v].x < 0) ok = false;  // isolated vertices are not coarsened
+    if (!ok || fine_of.size() == (size_t)fine->nV) break;
+    auto L = std::make_unique<Level>();
+    const int nc = (int)fine_of.size();
+    RC_TRY(L->curve.init(nc, (int)cedges.size() / 2, cedges.data()));
+    RC_TRY(dalloc(&L->fine_of, nc));
+    RC_TRY(dalloc(&L->prolong, fine->nV));
+    RC_TRY(dalloc(&L->gamma, 3 * (size_t)nc));
+    RC_HIP(hipMemcpy(L->fine_of, fine_of.data(), sizeof(int) * nc, hipMemcpyHostToDevice));
+    RC_HIP(hipMemcpy(L->prolong, prolong.data(), sizeof(int2) * fine->nV, hipMemcpyHostToDevice));
+    std::vector<std::vector<int>> lists(nc);
+    for (int v = 0; v < fine->nV; ++v) {
+      lists[prolong[v].x].push_back(v);
+      if (prolong[v].y != prolong[v].x) lists[prolong[v].y].push_back(v);
+    }
+    std::vector<int> off(nc + 1, 0), idx;
+    for (int i = 0; i < nc; ++i) {
+      off[i + 1] = off[i] + (int)lists[i].size();
+      idx.insert(idx.end(), lists[i].begin(), lists[i].end());
+    }
+    RC_TRY(dalloc(&L->restr_off, nc + 1));
+    RC_TRY(dalloc(&L->restr_idx, idx.size()));
+    RC_HIP(hipMemcpy(L->restr_off, off.data(), sizeof(int) * (nc + 1), hipMemcpyHostToDevice));
+    RC_HIP(hipMemcpy(L->restr_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice));
+    // the level's own constraints (same kinds as the finest level)
+    RC_TRY(cons_alloc(c, L->curve, L->cons, c->cons.mask));
+    if (c->cons.bary)
+      RC_HIP(hipMemcpy(L->cons.x0, c->cons.x0, sizeof(double) * 3, hipMemcpyDeviceToDevice));
+    c->levels.push_back(std::move(L));
+    fine = &c->levels.back()->curve;
+  }
+  const int nl = (int)c->levels.size();
+  c->mg.assign(nl, MGLevelState());
+  for (int l = 0; l < nl; ++l) {
+    const int n = level_curve(c, l).nV;
+    MGLevelState& st = c->mg[l];
+    RC_TRY(dalloc(&st.diag, n));
+    double** bufs[] = {&st.x, &st.b, &st.r, &st.d, &st.t, &st.pw};
+    for (double** b : bufs) RC_TRY(dalloc(b, 3 * (size_t)n));
+    hipLaunchKernelGGL(k_fill_pattern, dim3(cdiv(3 * n, 256)), dim3(256), 0, c->stream, st.pw, 3 * n, 12345u + l);
+  }
+  c->mg_built = true;
+  return RC_OK;
+}
+
+static rc_status apply_A(rc_ctx* c, const Curve& cv, const double* X, double* Y, rc_dtype prec) {
+  return launch_sobolev(cv, c->alpha, c->beta, prec, X, Y, nullptr, c->stream);
+}
+
+static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
+  RC_TRY(mg_build(c));
+  hipStream_t s = c->stream;
+  const int nl = (int)c->levels.size();
+  const double* g = gamma;
+  for (int l = 1; l < nl; ++l) {
+    Level& L = *c->levels[l];
+    hipLaunchKernelGGL(k_gather_coarse, dim3(cdiv(L.curve.nV, 256)), dim3(256), 0, s, g, L.fine_of, L.curve.nV,
+                       L.gamma);
+    g = L.gamma;
+  }
+  for (int l = 0; l < nl; ++l) {
+    const Curve& cv = level_curve(c, l);
+    const double* gl = l == 0 ? gamma : c->levels[l]->gamma;
+    RC_TRY(launch_geometry(cv, gl, RC_F32, s));
+    if (l > 0) RC_TRY(cons_prepare(c, cv, level_cons(c, l), gl));
+  }
+  const rc_dtype prec = c->dtype;
+  for (int l = 0; l < nl - 1; ++l) {
+    const Curve& cv = level_curve(c, l);
+    Cons& K = level_cons(c, l);
+    MGLevelState& st = c->mg[l];
+    const int n = cv.nV;
+    RC_TRY(launch_sobolev(cv, c->alpha, c->beta, prec, st.pw, st.t, st.diag, s));
+    // lambda_max of P D^-1 P A P by power iteration, warm-started from the last call's vector
+    double nrm = 0.0;
+    for (int it = 0; it < 12; ++it) {
+      cons_project(c, cv, K, st.pw, st.pw);
+      RC_TRY(launch_sobolev(cv, c->alpha, c->beta, prec, st.pw, st.t, nullptr, s));
+      cons_project(c, cv, K, st.t, st.t);
+      vec_scale_diag_inv(st.t, st.diag, st.d, n, s);
+      cons_project(c, cv, K, st.d, st.d);
+      vec_dot(st.d, st.d, 3 * n, c->red, c->scal, s);
+      double h;
+      RC_TRY(fetch(c, c->scal, &h, 1));
+      nrm = std::sqrt(h);
+      if (!(nrm > 0)) {
+        set_error("multigrid setup: zero operator");
+        return RC_ERR_SINGULAR;
+      }
+      vec_axpby(1.0 / nrm, st.d, 0.0, st.pw, 3 * n, s);
+    }
+    st.lmax = 1.1 * nrm;
+    if (trace_on()) fprintf(stderr, "[rc mg] level %d n %d lmax %.6e\n", l, n, nrm);
+  }
+  RC_TRY(dense_prepare(c, level_curve(c, nl - 1), level_cons(c, nl - 1), c->coarse,
+                       nl == 1 ? gamma : c->levels[nl - 1]->gamma));
+  return RC_OK;
+}
+
+// Projected Chebyshev smoothing of P A_l P x = b (b in range(P)) on level l.
+static rc_status cheb_smooth(rc_ctx* c, int l, double* x, const double* b, bool x_zero) {
+  const Curve& cv = level_curve(c, l);
+  Cons& K = level_cons(c, l);
+  MGLevelState& st = c->mg[l];
+  hipStream_t s = c->stream;
+  const int n = cv.nV, n3 = 3 * n;
+  const double lmax = st.lmax, lmin = 0.2 * lmax;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  if (x_zero) {
+    vec_copy(b, st.r, n3, s);
+    hipMemsetAsync(x, 0, sizeof(double) * n3, s);
+  } else {
+    RC_TRY(apply_A(c, cv, x, st.r, c->dtype));
+    vec_axpby(1.0, b, -1.0, st.r, n3, s);
+    cons_project(c, cv, K, st.r, st.r);
+  }
+  hipLaunchKernelGGL(k_cheb_init, dim3(cdiv(n3, 256)), dim3(256), 0, s, st.r, st.diag, 1.0 / theta, n, st.d);
+  cons_project(c, cv, K, st.d, st.d);
+  const int deg = c->cheb_deg;
+  for (int k = 0; k < deg; ++k) {
+    vec_axpby(1.0, st.d, 1.0, x, n3, s);
+    if (k == deg - 1) break;
+    RC_TRY(apply_A(c, cv, st.d, st.t, c->dtype));
+    cons_project(c, cv, K, st.t, st.t);
+    vec_axpby(-1.0, st.t, 1.0, st.r, n3, s);
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    // d = c1 d + c2 P D^-1 r (d is already in range(P))
+    hipLaunchKernelGGL(k_cheb_update, dim3(cdiv(n3, 256)), dim3(256), 0, s, st.r, st.diag, rn * rho,
+                       2.0 * rn / delta, n, st.d);
+    cons_project(c, cv, K, st.d, st.d);
+    rho = rn;
+  }
+  return RC_OK;
+}
+
+static rc_status vcycle(rc_ctx* c, int l, const double* b, double* x) {
+  hipStream_t s = c->stream;
+  const int nl = (int)c->levels.size();
+  if (l == nl - 1) {
+    dense_solve(c, c->coarse, b, x);
+    return RC_OK;
+  }
+  const Curve& cv = level_curve(c, l);
+  Cons& K = level_cons(c, l);
+  MGLevelState& st = c->mg[l];
+  const int n3 = 3 * cv.nV;
+  RC_TRY(cheb_smooth(c, l, x, b, true));
+  RC_TRY(apply_A(c, cv, x, st.t, c->dtype));
+  vec_axpby(1.0, b, -1.0, st.t, n3, s);  // t = b - A x
+  cons_project(c, cv, K, st.t, st.t);
+  Level& C = *c->levels[l + 1];
+  MGLevelState& sc = c->mg[l + 1];
+  hipLaunchKernelGGL(k_restrict, dim3(cdiv(C.curve.nV, 256)), dim3(256), 0, s, C.restr_off, C.restr_idx, C.prolong,
+                     C.curve.nV, st.t, sc.b);
+  cons_project(c, C.curve, C.cons, sc.b, sc.b);
+  RC_TRY(vcycle(c, l + 1, sc.b, sc.x));
+  hipLaunchKernelGGL(k_prolong, dim3(cdiv(cv.nV, 256)), dim3(256), 0, s, C.prolong, cv.nV, sc.x, st.t);
+  cons_project(c, cv, K, st.t, st.t);
+  vec_axpby(1.0, st.t, 1.0, x, n3, s);
+  RC_TRY(cheb_smooth(c, l, x, b, false));
+  return RC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// projected PCG:  P Abar P y = P b, y in range(P)   (App. B.3.3)
+// ---------------------------------------------------------------------------
+static rc_status precondition(rc_ctx* c, int kind, const double* r, double* z) {
+  if (kind == RC_SOLVE_PCG_MG) {
+    MGLevelState& st = c->mg[0];
+    vec_copy(r, st.b, 3 * c->nV, c->stream);
+    return vcycle(c, 0, st.b, z);
+  }
+  vec_scale_diag_inv(r, c->diag, z, c->nV, c->stream);
+  cons_project(c, c->curve, c->cons, z, z);
+  return RC_OK;
+}
+
+static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve_opts& o, int* iters_out,
+                           double* res_out) {
+  hipStream_t s = c->stream;
+  const int n3 = 3 * c->nV;
+  const rc_dtype op = o.op_f64 ? RC_F64 : c->dtype;
+  double *r = c->r, *z = c->z, *p = c->p, *q = c->q;
+  cons_project(c, c->curve, c->cons, b, c->tmp2);  // P b
+  vec_dot(c->tmp2, c->tmp2, n3, c->red, c->scal, s);
+  double bb;
+  RC_TRY(fetch(c, c->scal, &bb, 1));
+  const double bn = std::sqrt(bb);
+  hipMemsetAsync(x, 0, sizeof(double) * n3, s);
+  *iters_out = 0;
+  *res_out = 0.0;
+  if (!(bn > 0)) return RC_OK;
+  vec_copy(c->tmp2, r, n3, s);
+  int it = 0;
+  double res = 1.0;
+  bool converged = false;
+  while (it < o.max_iter && !converged) {
+    RC_TRY(precondition(c, o.solver, r, z));
+    vec_copy(z, p, n3, s);
+    vec_dot(r, z, n3, c->red, c->scal, s);
+    double rz;
+    RC_TRY(fetch(c, c->scal, &rz, 1));
+    int since = 0;
+    while (it < o.max_iter) {
+      RC_TRY(apply_A(c, c->curve, p, q, op));
+      cons_project(c, c->curve, c->cons, q, q);
+      vec_dot(p, q, n3, c->red, c->scal, s);
+      double pq;
+      RC_TRY(fetch(c, c->scal, &pq, 1));
+      if (!(pq > 0)) {
+        if (trace_on()) fprintf(stderr, "[rc pcg] it %d breakdown p.q = %.3e\n", it, pq);
+        break;
+      }
+      const double al = rz / pq;
+      vec_axpby(al, p, 1.0, x, n3, s);
+      vec_axpby(-al, q, 1.0, r, n3, s);
+      ++it;
+      ++since;
+      vec_dot(r, r, n3, c->red, c->scal, s);
+      double rr;
+      RC_TRY(fetch(c, c->scal, &rr, 1));
+      res = std::sqrt(rr) / bn;
+      if (trace_on()) fprintf(stderr, "[rc pcg] it %d rec-res %.3e\n", it, res);
+      if (res < o.tol || (o.replace_every > 0 && since >= o.replace_every)) {
+        // FP64 true residual r = P (b - Abar x); restart the recurrence from it
+        RC_TRY(apply_A(c, c->curve, x, c->tmp, RC_F64));
+        vec_copy(b, r, n3, s);
+        vec_axpby(-1.0, c->tmp, 1.0, r, n3, s);
+        cons_project(c, c->curve, c->cons, r, r);
+        vec_dot(r, r, n3, c->red, c->scal, s);
+        RC_TRY(fetch(c, c->scal, &rr, 1));
+        res = std::sqrt(rr) / bn;
+        if (trace_on()) fprintf(stderr, "[rc pcg] it %d TRUE-res %.3e\n", it, res);
+        if (res < o.tol) converged = true;
+        break;
+      }
+      RC_TRY(precondition(c, o.solver, r, z));
+      vec_dot(r, z, n3, c->red, c->scal, s);
+      double rzn;
+      RC_TRY(fetch(c, c->scal, &rzn, 1));
+      vec_axpby(1.0, z, rzn / rz, p, n3, s);
+      rz = rzn;
+    }
+    if (since == 0) break;
+  }
+  *iters_out = it;
+  *res_out = res;
+  if (!converged) {
+    set_error("projected PCG did not reach the tolerance");
+    return RC_ERR_NOT_CONVERGED;
+  }
+  return RC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// entry points used by the C ABI
+// ---------------------------------------------------------------------------
+rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o) {
+  RC_TRY(load_geometry(c, gamma));
+  RC_TRY(cons_prepare(c, c->curve, c->cons, gamma));
+  if (o.solver == RC_SOLVE_DENSE) return dense_prepare(c, c->curve, c->cons, c->dense, gamma);
+  if (o.solver == RC_SOLVE_PCG_MG) {
+    if (c->mg_min != o.mg_min_vertices) {
+      mg_free(c);
+      c->mg_min = o.mg_min_vertices;
+    }
+    c->cheb_deg = o.cheb_degree;
+    RC_TRY(mg_prepare(c, gamma));
+    return load_geometry(c, gamma);
+  }
+  return launch_sobolev(c->curve, c->alpha, c->beta, c->dtype, c->x, c->tmp, c->diag, c->stream);
+}
+
+rc_status solve_prepared(rc_ctx* c, const double* rhs, double* out, const rc_solve_opts& o, int* iters,
+                         double* res) {
+  if (o.solver == RC_SOLVE_DENSE) {
+    dense_solve(c, c->dense, rhs, out);
+    *iters = 0;
+    *res = 0.0;
+    return sync(c);
+  }
+  return pcg_solve(c, rhs, out, o, iters, res);
+}
+
+// Projection increment for the violation phi (external order): eq.
+// ConstraintSaddlePointProblem, through eq. SaddleSolutionTransformation on
+// the PCG paths (z = C^T (C C^T)^-1 (-phi), y from the projected system with
+// right-hand side Abar z, x = z - y).
+static rc_status projection_increment(rc_ctx* c, const double* phi, double* x, const rc_solve_opts& o, int* iters) {
+  hipStream_t s = c->stream;
+  const int n3 = 3 * c->nV, k = c->cons.k;
+  *iters = 0;
+  if (o.solver == RC_SOLVE_DENSE) {
+    dense_increment(c, c->dense, phi, x);
+    return RC_OK;
+  }
+  hipLaunchKernelGGL(k_negate, dim3(cdiv(k, 256)), dim3(256), 0, s, phi, c->phi + k, k);
+  cons_min_norm(c, c->phi + k, c->zmin);
+  RC_TRY(apply_A(c, c->curve, c->zmin, c->inc, RC_F64));
+  double res = 0.0;
+  rc_status st = pcg_solve(c, c->inc, c->x, o, iters, &res);
+  if (st != RC_OK && st != RC_ERR_NOT_CONVERGED) return st;
+  vec_copy(c->zmin, x, n3, s);
+  vec_axpby(-1.0, c->x, 1.0, x, n3, s);
+  return RC_OK;
+}
+
+rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, const double* g, const rc_ls_opts& ls,
+                      const rc_solve_opts& so, LsResult* out) {
+  hipStream_t s = c->stream;
+  const int n3 = 3 * c->nV, k = c->cons.k;
+  // scal[16] keeps |g|^2 for the trial points; the solvers use scal[0..15]
+  vec_dot(g, g, n3, c->red, c->scal + 16, s);
+  vec_dot(dE, g, n3, c->red, c->scal + 17, s);
+  double h[2];
+  RC_TRY(fetch(c, c->scal + 16, h, 2));
+  if (!(h[0] > 0)) {
+    set_error("zero gradient");
+    return RC_ERR_LINESEARCH;
+  }
+  const double slope = h[1] / std::sqrt(h[0]);
+  // per-row projection tolerances relative to the mean edge length at gamma
+  std::vector<double> phi_h(std::max(k, 1));
+  double Ltot = 0.0;
+  {
+    std::vector<double> ga(4 * (size_t)c->nE);
+    RC_TRY(load_geometry(c, gamma));
+    RC_HIP(hipMemcpyAsync(ga.data(), c->curve.gd.a, sizeof(double) * 4 * c->nE, hipMemcpyDeviceToHost, s));
+    RC_TRY(sync(c));
+    for (int I = 0; I < c->nE; ++I) Ltot += ga[4 * I + 3];
+  }
+  const double lbar = Ltot / std::max(1, c->nE);
+  const Cons& K = c->cons;
+  double tau = ls.tau0;
+  for (int bt = 0; bt <= ls.max_backtracks; ++bt) {
+    vec_trial(gamma, g, c->scal + 16, tau, c->trial, n3, s);
+    bool ok = (k == 0);
+    int it = 0;
+    for (; k > 0 && it <= ls.max_proj_iter; ++it) {
+      cons_values(c, c->trial, c->phi);
+      RC_TRY(fetch(c, c->phi, phi_h.data(), k));
+      bool done = true;
+      for (int i = 0; i < k; ++i) {
+        double tol = ls.proj_tol * lbar;
+        if (K.bary && i < 3) tol *= Ltot;             // barycenter rows carry units of length^2
+        else if (K.total && i == 3 * K.bary) tol *= Ltot / lbar;  // total length: relative to L
+        if (!std::isfinite(phi_h[i]) || std::fabs(phi_h[i]) > tol) done = false;
+      }
+      if (done) {
+        ok = true;
+        break;
+      }
+      if (it == ls.max_proj_iter) break;
+      int pit = 0;
+      RC_TRY(load_geometry(c, gamma));
+      RC_TRY(projection_increment(c, c->phi, c->dx, so, &pit));
+      out->proj_solve_iters += pit;
+      vec_axpby(1.0, c->dx, 1.0, c->trial, n3, s);
+    }
+    if (ok) {
+      RC_TRY(load_geometry(c, c->trial));
+      RC_TRY(launch_tpe(c->curve, c->alpha, c->beta, c->dtype, false, c->scal + 18, nullptr, s));
+      double E1;
+      RC_TRY(fetch(c, c->scal + 18, &E1, 1));
+      if (std::isfinite(E1) && E1 <= E0 - ls.c_armijo * tau * slope) {
+        vec_copy(c->trial, gamma, n3, s);
+        RC_TRY(sync(c));
+        out->tau = tau;
+        out->E1 = E1;
+        out->backtracks = bt;
+        out->proj_iters = it;
+        return RC_OK;
+      }
+    }
+    tau *= ls.shrink;
+  }
+  set_error("line search found no admissible step");
+  out->backtracks = ls.max_backtracks;
+  return RC_ERR_LINESEARCH;
+}
+
+}  // namespace rc
