@@ -86,6 +86,8 @@ typedef struct {
   int32_t max_backtracks;
   int32_t max_proj_iter; /* projection iterations per trial step */
   double proj_tol;       /* relative projection tolerance (times mean edge length) */
+  double proj_solve_tol; /* PCG tolerance of the projection increments: C x = -Phi holds exactly
+                            whatever it is; it only sets how close x is to the A-norm minimiser */
 } rc_ls_opts;
 
 typedef struct {

@@ -95,6 +95,7 @@ void rc_default_ls_opts(rc_ls_opts* o) {
   o->max_backtracks = 30;
   o->max_proj_iter = 10;
   o->proj_tol = 1e-10;
+  o->proj_solve_tol = 1e-3;
 }
 
 const char* rc_last_error(void) { return rc::last_error(); }

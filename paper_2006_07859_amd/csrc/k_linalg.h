@@ -13,9 +13,13 @@ int dot_scratch_size(int m);
 void vec_trial(const double* gamma, const double* g, const double* gg, double tau, double* out, int n,
                hipStream_t s);
 
-// Tridiagonal solve (one workgroup, partition method); scratch of 4 n doubles.
-void tridiag_solve(const double* a, const double* d, const double* c, const double* b, double* y, int n,
-                   double* scratch4n, hipStream_t s);
+// Tridiagonal systems: factorisation (l, 1/u; info[0] = 0 on success) and
+// solves by parallel scans in one workgroup.
+void tridiag_factor(const double* a, const double* d, const double* c, int n, double* lo, double* uinv, int* info,
+                    hipStream_t s);
+void tridiag_solve(const double* lo, const double* uinv, const double* c, const double* b, double* y, int n,
+                   hipStream_t s);
+void dense_gemv(const double* A, const double* x, double* y, int n, hipStream_t s);
 
 // constraint pieces
 void cons_geometry(const double* gamma, const int2* edges, int nE, double* geo, hipStream_t s);

@@ -182,15 +182,21 @@ void dense_cholesky(double* A, int n, int* info, hipStream_t s) {
   }
 }
 
-// L L^T X = B, B is n x m row-major, one workgroup, column sweeps.
-__global__ void k_chol_solve(const double* __restrict__ L, double* __restrict__ B, int n, int m) {
+// L L^T X = B, B is n x m row-major: column sweeps, each workgroup owns up
+// to 16 right-hand-side columns.
+constexpr int kSolveCols = 16;
+
+__global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ L, double* __restrict__ B, int n,
+                                                      int m) {
+  const int c0 = blockIdx.x * kSolveCols;
+  const int mc = min(kSolveCols, m - c0);
   // forward: L y = b
   for (int j = 0; j < n; ++j) {
     const double ljj = L[(size_t)j * n + j];
-    for (int c = threadIdx.x; c < m; c += blockDim.x) B[(size_t)j * m + c] /= ljj;
+    if (threadIdx.x < mc) B[(size_t)j * m + c0 + threadIdx.x] /= ljj;
     __syncthreads();
-    for (int idx = threadIdx.x; idx < (n - j - 1) * m; idx += blockDim.x) {
-      int i = j + 1 + idx / m, c = idx % m;
+    for (int idx = threadIdx.x; idx < (n - j - 1) * mc; idx += blockDim.x) {
+      int i = j + 1 + idx / mc, c = c0 + idx % mc;
       B[(size_t)i * m + c] -= L[(size_t)i * n + j] * B[(size_t)j * m + c];
     }
     __syncthreads();
@@ -198,10 +204,10 @@ __global__ void k_chol_solve(const double* __restrict__ L, double* __restrict__ 
   // backward: L^T x = y
   for (int j = n - 1; j >= 0; --j) {
     const double ljj = L[(size_t)j * n + j];
-    for (int c = threadIdx.x; c < m; c += blockDim.x) B[(size_t)j * m + c] /= ljj;
+    if (threadIdx.x < mc) B[(size_t)j * m + c0 + threadIdx.x] /= ljj;
     __syncthreads();
-    for (int idx = threadIdx.x; idx < j * m; idx += blockDim.x) {
-      int i = idx / m, c = idx % m;
+    for (int idx = threadIdx.x; idx < j * mc; idx += blockDim.x) {
+      int i = idx / mc, c = c0 + idx % mc;
       B[(size_t)i * m + c] -= L[(size_t)j * n + i] * B[(size_t)j * m + c];
     }
     __syncthreads();
@@ -209,119 +215,164 @@ __global__ void k_chol_solve(const double* __restrict__ L, double* __restrict__ 
 }
 
 void dense_chol_solve(const double* L, double* B, int n, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, s, L, B, n, m);
+  hipLaunchKernelGGL(k_chol_solve, dim3(cdiv(m, kSolveCols)), dim3(1024), 0, s, L, B, n, m);
 }
 
-// C[m x n] = op(A) B + beta C, A is m x k (or k x m if transA), B is k x n, row-major.
+// C[m x n] = op(A) op(B) + beta C, row-major; op(A) is m x k (A stored k x m
+// when transA), op(B) is k x n (B stored n x k when transB).
 __global__ void k_gemm(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C, int m,
-                       int n, int k, double beta, int transA) {
+                       int n, int k, double beta, int transA, int transB) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   int i = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= m || j >= n) return;
   double s = 0.0;
-  if (transA)
-    for (int p = 0; p < k; ++p) s += A[(size_t)p * m + i] * B[(size_t)p * n + j];
-  else
-    for (int p = 0; p < k; ++p) s += A[(size_t)i * k + p] * B[(size_t)p * n + j];
+  for (int p = 0; p < k; ++p) {
+    const double av = transA ? A[(size_t)p * m + i] : A[(size_t)i * k + p];
+    const double bv = transB ? B[(size_t)j * k + p] : B[(size_t)p * n + j];
+    s += av * bv;
+  }
   C[(size_t)i * n + j] = s + (beta != 0.0 ? beta * C[(size_t)i * n + j] : 0.0);
 }
 
 void dense_gemm(const double* A, const double* B, double* C, int m, int n, int k, double beta, bool transA,
-                hipStream_t s) {
+                hipStream_t s, bool transB) {
   dim3 b(16, 16), g(cdiv(n, 16), cdiv(m, 16));
-  hipLaunchKernelGGL(k_gemm, g, b, 0, s, A, B, C, m, n, k, beta, transA ? 1 : 0);
+  hipLaunchKernelGGL(k_gemm, g, b, 0, s, A, B, C, m, n, k, beta, transA ? 1 : 0, transB ? 1 : 0);
+}
+
+// y = A x for a dense n x n row-major A and a vector x (one wave per row).
+__global__ __launch_bounds__(256) void k_gemv(const double* __restrict__ A, const double* __restrict__ x,
+                                              double* __restrict__ y, int n) {
+  const int row = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += A[(size_t)row * n + j] * x[j];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) y[row] = s;
+}
+
+void dense_gemv(const double* A, const double* x, double* y, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv, dim3(cdiv(n, 4)), dim3(256), 0, s, A, x, y, n);
 }
 
 // ---------------------------------------------------------------------------
-// tridiagonal solve: partition method in one workgroup
+// tridiagonal systems: Thomas factorisation once, solves by parallel scans
 // ---------------------------------------------------------------------------
-// Rows k < n: a[k] y[k-1] + d[k] y[k] + c[k] y[k+1] = b[k], with a[0] = c[n-1] = 0
-// (zero couplings also separate independent segments).  The rows are split
-// into nc chunks; each thread eliminates its chunk for the right-hand side
-// and the two coupling spikes, thread 0 solves the 2-unknowns-per-chunk
-// reduced system, and every thread then back-substitutes its chunk.
-constexpr int kTriThreads = 256;
+// Rows k < n: a[k] y[k-1] + d[k] y[k] + c[k] y[k+1] = b[k] with a[0] = c[n-1] = 0
+// (zero couplings also separate independent segments).  The factorisation
+// l[k] = a[k] / u[k-1], u[k] = d[k] - l[k] c[k-1] is a nonlinear recurrence and
+// runs in one thread once per system; it stores l and 1/u.  A solve is two
+// first-order linear recurrences, forward  z[k] = b[k] - l[k] z[k-1]  and
+// backward  y[k] = (z[k] - c[k] y[k+1]) / u[k].  Each is an affine map per row;
+// one workgroup composes the maps of contiguous chunks per thread, scans the
+// chunk composites across the workgroup in LDS, and then replays its chunk.
+// The system is symmetric positive definite (a constraint Gram matrix), so
+// the factorisation needs no pivoting.
+__global__ void k_tridiag_factor(const double* __restrict__ a, const double* __restrict__ d,
+                                 const double* __restrict__ c, int n, double* __restrict__ lo,
+                                 double* __restrict__ uinv, int* __restrict__ info) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double u_prev = 1.0, c_prev = 0.0;
+  int bad = 0;
+  for (int k = 0; k < n; ++k) {
+    const double l = (k == 0) ? 0.0 : a[k] / u_prev;
+    const double u = d[k] - l * c_prev;
+    if (!(u > 0.0)) bad = k + 1;
+    lo[k] = l;
+    uinv[k] = 1.0 / u;
+    u_prev = u;
+    c_prev = c[k];
+  }
+  info[0] = bad;
+}
 
-__global__ __launch_bounds__(kTriThreads) void k_tridiag(const double* __restrict__ a, const double* __restrict__ d,
-                                                         const double* __restrict__ c, const double* __restrict__ b,
-                                                         double* __restrict__ y, int n, double* __restrict__ G,
-                                                         double* __restrict__ Vs, double* __restrict__ Ws,
-                                                         double* __restrict__ Cp) {
-  __shared__ double sF[kTriThreads], sGl[kTriThreads];
-  __shared__ double rF[3][kTriThreads], rG[3][kTriThreads];  // (g, v, w) at chunk first/last rows
-  const int nc = max(1, min(kTriThreads, n / 8));
-  const int j = threadIdx.x;
-  if (j < nc) {
-    const int k0 = (int)(((long long)j * n) / nc), k1 = (int)(((long long)(j + 1) * n) / nc);
-    double cp = 0.0, gp = 0.0, vp = 0.0, wp = 0.0;
-    for (int k = k0; k < k1; ++k) {
-      const double ak = (k == k0) ? 0.0 : a[k];
-      const double den = d[k] - ak * cp;
-      const double inv = 1.0 / den;
-      const double vin = (k == k0) ? a[k] : 0.0;
-      const double win = (k == k1 - 1) ? c[k] : 0.0;
-      gp = (b[k] - ak * gp) * inv;
-      vp = (vin - ak * vp) * inv;
-      wp = (win - ak * wp) * inv;
-      cp = (k == k1 - 1) ? 0.0 : c[k] * inv;
-      Cp[k] = cp;
-      G[k] = gp;
-      Vs[k] = vp;
-      Ws[k] = wp;
+constexpr int kTriThreads = 1024;
+
+__global__ __launch_bounds__(kTriThreads) void k_tridiag_solve(const double* __restrict__ lo,
+                                                                const double* __restrict__ uinv,
+                                                                const double* __restrict__ c,
+                                                                const double* __restrict__ b, double* __restrict__ y,
+                                                                int n) {
+  __shared__ double sA[kTriThreads], sB[kTriThreads];
+  const int t = threadIdx.x;
+  const int m = (n + kTriThreads - 1) / kTriThreads;
+  const int k0 = min(n, t * m), k1 = min(n, k0 + m);
+  // forward: z[k] = -l[k] z[k-1] + b[k]; chunk composite z_out = A z_in + B
+  double A = 1.0, B = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const double l = lo[k];
+    A = -l * A;
+    B = -l * B + b[k];
+  }
+  sA[t] = A;
+  sB[t] = B;
+  __syncthreads();
+  // inclusive scan of composites (later chunk applied after earlier ones)
+  for (int off = 1; off < kTriThreads; off <<= 1) {
+    double pa = 1.0, pb = 0.0;
+    if (t >= off) {
+      pa = sA[t - off];
+      pb = sB[t - off];
     }
-    double gn = 0.0, vn = 0.0, wn = 0.0;
-    for (int k = k1 - 1; k >= k0; --k) {
-      const double cpk = Cp[k];
-      gn = G[k] - cpk * gn;
-      vn = Vs[k] - cpk * vn;
-      wn = Ws[k] - cpk * wn;
-      G[k] = gn;
-      Vs[k] = vn;
-      Ws[k] = wn;
+    __syncthreads();
+    if (t >= off) {
+      const double ca = sA[t], cb = sB[t];
+      sA[t] = ca * pa;
+      sB[t] = ca * pb + cb;
     }
-    rF[0][j] = G[k0]; rF[1][j] = Vs[k0]; rF[2][j] = Ws[k0];
-    rG[0][j] = G[k1 - 1]; rG[1][j] = Vs[k1 - 1]; rG[2][j] = Ws[k1 - 1];
+    __syncthreads();
+  }
+  double zin = (t > 0) ? sB[t - 1] : 0.0;  // z before the chunk (z[-1] = 0)
+  __syncthreads();
+  for (int k = k0; k < k1; ++k) {
+    zin = -lo[k] * zin + b[k];
+    y[k] = zin;
   }
   __syncthreads();
-  if (j == 0) {
-    // F_j = gF - vF G_{j-1} - wF F_{j+1};  G_j = gG - vG G_{j-1} - wG F_{j+1}
-    double al = 0.0, be = 0.0;  // G_{j-1} = al + be F_j
-    for (int q = 0; q < nc; ++q) {
-      const double den = 1.0 + rF[1][q] * be;
-      const double phi = (rF[0][q] - rF[1][q] * al) / den;
-      const double psi = -rF[2][q] / den;
-      const double na = rG[0][q] - rG[1][q] * (al + be * phi);
-      const double nbv = -rG[1][q] * be * psi - rG[2][q];
-      sF[q] = phi;   // F_q = phi + psi F_{q+1}
-      sGl[q] = psi;
-      rG[0][q] = na;  // G_q = na + nb F_{q+1}
-      rG[1][q] = nbv;
-      al = na;
-      be = nbv;
-    }
-    double Fn = 0.0;
-    for (int q = nc - 1; q >= 0; --q) {
-      const double Fq = sF[q] + sGl[q] * Fn;
-      const double Gq = rG[0][q] + rG[1][q] * Fn;
-      sF[q] = Fq;
-      sGl[q] = Gq;
-      Fn = Fq;
-    }
+  // backward: y[k] = -c[k] uinv[k] y[k+1] + z[k] uinv[k], scanned from the end
+  A = 1.0;
+  B = 0.0;
+  for (int k = k1 - 1; k >= k0; --k) {
+    const double ui = uinv[k];
+    A = -c[k] * ui * A;
+    B = -c[k] * ui * B + y[k] * ui;
   }
+  sA[t] = A;
+  sB[t] = B;
   __syncthreads();
-  if (j < nc) {
-    const int k0 = (int)(((long long)j * n) / nc), k1 = (int)(((long long)(j + 1) * n) / nc);
-    const double GL = (j > 0) ? sGl[j - 1] : 0.0;
-    const double FR = (j + 1 < nc) ? sF[j + 1] : 0.0;
-    for (int k = k0; k < k1; ++k) y[k] = G[k] - Vs[k] * GL - Ws[k] * FR;
+  for (int off = 1; off < kTriThreads; off <<= 1) {
+    double pa = 1.0, pb = 0.0;
+    if (t + off < kTriThreads) {
+      pa = sA[t + off];
+      pb = sB[t + off];
+    }
+    __syncthreads();
+    if (t + off < kTriThreads) {
+      const double ca = sA[t], cb = sB[t];
+      sA[t] = ca * pa;
+      sB[t] = ca * pb + cb;
+    }
+    __syncthreads();
+  }
+  double yin = (t + 1 < kTriThreads) ? sB[t + 1] : 0.0;  // y after the chunk (y[n] = 0)
+  for (int k = k1 - 1; k >= k0; --k) {
+    const double ui = uinv[k];
+    yin = -c[k] * ui * yin + y[k] * ui;
+    y[k] = yin;
   }
 }
 
-void tridiag_solve(const double* a, const double* d, const double* c, const double* b, double* y, int n,
-                   double* scratch4n, hipStream_t s) {
+void tridiag_factor(const double* a, const double* d, const double* c, int n, double* lo, double* uinv, int* info,
+                    hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kTriThreads), 0, s, a, d, c, b, y, n, scratch4n, scratch4n + n,
-                     scratch4n + 2 * n, scratch4n + 3 * n);
+  hipLaunchKernelGGL(k_tridiag_factor, dim3(1), dim3(64), 0, s, a, d, c, n, lo, uinv, info);
+}
+
+void tridiag_solve(const double* lo, const double* uinv, const double* c, const double* b, double* y, int n,
+                   hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_tridiag_solve, dim3(1), dim3(kTriThreads), 0, s, lo, uinv, c, b, y, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -527,16 +578,6 @@ void cons_apply_CT(const double* geo, const int* inc_off, const int* inc, const 
 
 // y_p -= Z y_b (Z is np x nb column blocks: Z + r*np), and the small dense
 // border solve y_b = Sinv rhs_b, done by one thread (nb is small).
-__global__ void k_border_solve(const double* __restrict__ Sinv, const double* __restrict__ rhs, int nb,
-                               double* __restrict__ yb) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int i = 0; i < nb; ++i) {
-    double s = 0.0;
-    for (int j = 0; j < nb; ++j) s += Sinv[i * nb + j] * rhs[j];
-    yb[i] = s;
-  }
-}
-
 __global__ void k_sub_Zy(const double* __restrict__ Z, const double* __restrict__ yb, int nb, int np,
                          double* __restrict__ yp) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -546,15 +587,23 @@ __global__ void k_sub_Zy(const double* __restrict__ Z, const double* __restrict_
   yp[k] -= s;
 }
 
-__global__ void k_rhs_border(const double* __restrict__ wb, const double* __restrict__ dots, int nb,
-                             double* __restrict__ rhs) {
-  for (int r = threadIdx.x; r < nb; r += blockDim.x) rhs[r] = wb[r] - dots[r];
+// yb = Sinv (wb - dots): one workgroup, nb <= 128
+__global__ void k_border_fused(const double* __restrict__ Sinv, const double* __restrict__ wb,
+                               const double* __restrict__ dots, int nb, double* __restrict__ yb) {
+  __shared__ double rhs[128];
+  for (int r = threadIdx.x; r < nb; r += blockDim.x) rhs[r] = wb[r] - (dots ? dots[r] : 0.0);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < nb; ++j) s += Sinv[i * nb + j] * rhs[j];
+    yb[i] = s;
+  }
 }
 
 void cons_border_solve(const double* Sinv, const double* wb, const double* dots, double* rhs, int nb, double* yb,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_rhs_border, dim3(1), dim3(64), 0, s, wb, dots, nb, rhs);
-  hipLaunchKernelGGL(k_border_solve, dim3(1), dim3(64), 0, s, Sinv, rhs, nb, yb);
+  (void)rhs;
+  hipLaunchKernelGGL(k_border_fused, dim3(1), dim3(128), 0, s, Sinv, wb, dots, nb, yb);
 }
 
 void cons_sub_Zy(const double* Z, const double* yb, int nb, int np, double* yp, hipStream_t s) {

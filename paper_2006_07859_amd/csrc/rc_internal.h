@@ -160,6 +160,6 @@ void dense_cholesky(double* A, int n, int* info, hipStream_t s);
 void dense_chol_solve(const double* L, double* B, int n, int m, hipStream_t s);
 // C = A B (+ beta C): small dense FP64 GEMM, row-major, all device.
 void dense_gemm(const double* A, const double* B, double* C, int m, int n, int k, double beta,
-                bool transA, hipStream_t s);
+                bool transA, hipStream_t s, bool transB = false);
 
 }  // namespace rc

@@ -31,11 +31,12 @@ struct Cons {
 
 // Dense FP64 saddle solve on one curve: H = Abar + C^T C (Cholesky),
 // W = H^-1 C^T, S = C W.  Projected gradient with right-hand side b:
-// x = H^-1 b - W S^-1 W^T b; projection increment: x = -W S^-1 phi.
+// x = X b with X = H^-1 - W S^-1 W^T (kept explicitly, so a solve is one
+// matrix-vector product); projection increment: x = -W S^-1 phi.
 struct Dense {
   int nV = 0, k = 0;
   double *A = nullptr, *Cd = nullptr, *CtC = nullptr, *H = nullptr, *W = nullptr, *S = nullptr, *Sinv = nullptr,
-         *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
+         *X = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
   int* info = nullptr;
 };
 

@@ -253,7 +253,7 @@ rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask) {
   RC_TRY(dalloc(&k.Kpb, (size_t)std::max(k.nb, 1) * std::max(k.np, 1)));
   RC_TRY(dalloc(&k.Z, (size_t)std::max(k.nb, 1) * std::max(k.np, 1)));
   RC_TRY(dalloc(&k.Sinv, (size_t)std::max(k.nb * k.nb, 1)));
-  RC_TRY(dalloc(&k.tri_scratch, 4 * (size_t)std::max(k.np, 1)));
+  RC_TRY(dalloc(&k.tri_scratch, 2 * (size_t)std::max(k.np, 1) + 2));  // l and 1/u of the path block, info
   RC_TRY(dalloc(&k.wp, k.np));
   RC_TRY(dalloc(&k.yp, k.np));
   RC_TRY(dalloc(&k.wb, std::max(k.nb, 1)));
@@ -299,14 +299,27 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma)
   cons_border_rows(k.geo, cv.inc_off, cv.inc, cv.edges, k.x0, nV, k.bary, k.total, k.cut_edge, k.ncut, k.rows,
                    k.nb, s);
   const int nb = k.nb, np = k.np;
-  if (np > 0) cons_path_coeffs(k.geo, cv.edges, k.path_edge, k.path_prev, np, k.ta, k.td, k.tc, s);
+  double* lo = k.tri_scratch;
+  double* uinv = k.tri_scratch + np;
+  int* tinfo = (int*)(k.tri_scratch + 2 * np);
+  if (np > 0) {
+    cons_path_coeffs(k.geo, cv.edges, k.path_edge, k.path_prev, np, k.ta, k.td, k.tc, s);
+    tridiag_factor(k.ta, k.td, k.tc, np, lo, uinv, tinfo, s);
+    int info = 0;
+    RC_HIP(hipMemcpyAsync(&info, tinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+    RC_TRY(sync(c));
+    if (info != 0) {
+      set_error("edge-length constraint Gram matrix is not positive definite");
+      return RC_ERR_SINGULAR;
+    }
+  }
   if (nb > 0) {
     for (int r = 0; r < nb; ++r)
       vec_dots(k.rows, 3 * nV, k.rows + (size_t)r * 3 * nV, 0, 3 * nV, nb, c->red, k.dots + r * nb, s);
     if (np > 0) {
       cons_path_apply(k.geo, cv.edges, k.path_edge, np, k.rows, nV, nb, k.Kpb, s);
       for (int r = 0; r < nb; ++r)
-        tridiag_solve(k.ta, k.td, k.tc, k.Kpb + (size_t)r * np, k.Z + (size_t)r * np, np, k.tri_scratch, s);
+        tridiag_solve(lo, uinv, k.tc, k.Kpb + (size_t)r * np, k.Z + (size_t)r * np, np, s);
       for (int r = 0; r < nb; ++r) vec_dots(k.Kpb, np, k.Z + (size_t)r * np, 0, np, nb, c->red, k.small + r * nb, s);
     }
     std::vector<double> S(nb * nb), kz(nb * nb, 0.0);
@@ -325,7 +338,7 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma)
 // (wp, wb) -> (yp, yb) = (C C^T)^-1 w
 static void cons_solve_K(rc_ctx* c, Cons& k) {
   hipStream_t s = c->stream;
-  if (k.np > 0) tridiag_solve(k.ta, k.td, k.tc, k.wp, k.yp, k.np, k.tri_scratch, s);
+  if (k.np > 0) tridiag_solve(k.tri_scratch, k.tri_scratch + k.np, k.tc, k.wp, k.yp, k.np, s);
   if (k.nb > 0) {
     if (k.np > 0) vec_dots(k.Kpb, k.np, k.yp, 0, k.np, k.nb, c->red, k.dots, s);
     else hipMemsetAsync(k.dots, 0, sizeof(double) * k.nb, s);
@@ -388,6 +401,7 @@ void dense_free(Dense& d) {
   dfree(d.t1);
   dfree(d.t2);
   dfree(d.t3);
+  dfree(d.X);
   dfree(d.info);
   d = Dense();
 }
@@ -413,6 +427,7 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
     RC_TRY(dalloc(&d.t1, (size_t)std::max(kk, 1)));
     RC_TRY(dalloc(&d.t2, (size_t)std::max(kk, 1)));
     RC_TRY(dalloc(&d.t3, (size_t)n));
+    RC_TRY(dalloc(&d.X, (size_t)n * n));
     RC_TRY(dalloc(&d.info, 1));
   }
   RC_TRY(launch_geometry(cv, gamma, RC_F32, s));
@@ -443,6 +458,9 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
     set_error("Cholesky of Abar + C^T C failed: Abar is not definite on null(C)");
     return RC_ERR_SINGULAR;
   }
+  // X = H^-1 (solve with the identity), then X -= W S^-1 W^T
+  hipLaunchKernelGGL(k_identity, dim3(cdiv(n * n, 256)), dim3(256), 0, s, d.X, n);
+  dense_chol_solve(d.H, d.X, n, n, s);
   if (kk > 0) {
     double* Ik;
     RC_TRY(dalloc(&Ik, (size_t)kk * kk));
@@ -459,22 +477,17 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
       return RC_ERR_SINGULAR;
     }
     RC_HIP(hipMemcpyAsync(d.Sinv, S.data(), sizeof(double) * kk * kk, hipMemcpyHostToDevice, s));
+    // X += (-W S^-1) W^T, with -W S^-1 staged in CtC (no longer needed)
+    dense_gemm(d.W, d.Sinv, d.CtC, n, kk, kk, 0.0, false, s);
+    vec_axpby(0.0, d.CtC, -1.0, d.CtC, n * kk, s);
+    dense_gemm(d.CtC, d.W, d.X, n, n, kk, 1.0, false, s, true);
   }
   return sync(c);
 }
 
 // x = H^-1 b - W S^-1 W^T b: the saddle solution with right-hand side (b, 0).
 static void dense_solve(rc_ctx* c, Dense& d, const double* b, double* x) {
-  hipStream_t s = c->stream;
-  const int n = 3 * d.nV, k = d.k;
-  vec_copy(b, x, n, s);
-  dense_chol_solve(d.H, x, n, 1, s);
-  if (k > 0) {
-    dense_gemm(d.Cd, x, d.t1, k, 1, n, 0.0, false, s);  // C H^-1 b = W^T b
-    dense_gemm(d.Sinv, d.t1, d.t2, k, 1, k, 0.0, false, s);
-    dense_gemm(d.W, d.t2, d.t3, n, 1, k, 0.0, false, s);
-    vec_axpby(-1.0, d.t3, 1.0, x, n, s);
-  }
+  dense_gemv(d.X, b, x, 3 * d.nV, c->stream);
 }
 
 // x = -W S^-1 phi: the saddle solution with right-hand side (0, -phi).
@@ -922,7 +935,9 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
       if (it == ls.max_proj_iter) break;
       int pit = 0;
       RC_TRY(load_geometry(c, gamma));
-      RC_TRY(projection_increment(c, c->phi, c->dx, so, &pit));
+      rc_solve_opts po = so;
+      if (ls.proj_solve_tol > 0) po.tol = ls.proj_solve_tol;
+      RC_TRY(projection_increment(c, c->phi, c->dx, po, &pit));
       out->proj_solve_iters += pit;
       vec_axpby(1.0, c->dx, 1.0, c->trial, n3, s);
     }
