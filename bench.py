@@ -83,11 +83,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--edges", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="step", choices=["step", "bh"],
+                    help="step: projected Sobolev steps on the 16,384-edge knot (default); "
+                         "bh: Barnes-Hut energy+differential on a 262,144-edge knot")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not supported "
                                    "(the sharding design is described in DESIGN.md)", "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.workload == "bh":
+        return bench_bh(args)
 
     import numpy as np
     import torch
@@ -188,6 +194,66 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, e, alpha, beta)
+    ctx.close()
+    print(json.dumps(out))
+
+
+def bench_bh(args):
+    """Barnes-Hut (theta = 0.25, leaves of 32) on a 262,144-edge knot, FP32."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2006_07859_amd import RC_F32, Context
+
+    n = 262144 if args.edges == 16384 else args.edges
+    alpha, beta, theta = 2.0, 4.5, 0.25
+    g, e, _ = gen.fourier_knot(n, seed=0)
+    g = gen.round_to_f32(g)
+    P = ordered_disjoint_pairs(e)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    ctx = Context(n, e, alpha, beta, RC_F32)
+    gamma = dev(g)
+    E = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dE = torch.zeros(n, 3, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        ctx.rc_bh_differential(gamma, theta, 32, E, dE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.rc_bh_differential(gamma, theta, 32, E, dE)
+    torch.cuda.synchronize()
+    T = (time.perf_counter() - t0) / args.steps
+    work = ctx.rc_bh_last_work()
+    # exact edge-midpoint sum (the theta -> 0 limit) for the error
+    Em = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dEm = torch.zeros_like(dE)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.rc_midpoint_differential(gamma, Em, dEm)
+    torch.cuda.synchronize()
+    Tm = time.perf_counter() - t1
+    err_E = abs(E.item() - Em.item()) / abs(Em.item())
+    err_G = (torch.linalg.norm(dE - dEm) / torch.linalg.norm(dEm)).item()
+    out = {
+        "metric": "exact-equivalent edge-pair evals/s (Barnes-Hut energy+grad)",
+        "value": P / T,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"fourier knot, {n} edges, (alpha,beta)=(2,4.5), Barnes-Hut theta=0.25, leaf 32, "
+                               f"BVH built on the device every evaluation", "edges": n, "ordered_pairs": P},
+        "interactions": work,
+        "exact_midpoint_ms": Tm * 1e3,
+        "error_vs_exact_midpoint": {"energy_rel": err_E, "differential_rel": err_G},
+    }
     ctx.close()
     print(json.dumps(out))
 

@@ -200,10 +200,16 @@ rc_status rc_step(rc_ctx* ctx, double* gamma, const rc_solve_opts* so, const rc_
  * (T_I, x_I) in R^6 built on the device, admissibility
  * r_x < theta |x_I - xbar_B| and r_T < theta (eq. BarnesHutCondition), far
  * field per eq. BVHNodeTPE, near field summed directly with the edge-midpoint
- * rule.  FP32 arithmetic.  leaf_size: edges per leaf (<= 64).
+ * rule.  FP32 arithmetic.  theta in (0, 0.5): then a target's own cluster is
+ * never admissible.  leaf_size in [1, 256]: most edges per leaf.
  * energy: device double [1]; dE: device double [nV][3]. */
 rc_status rc_bh_differential(rc_ctx* ctx, const double* gamma, double theta, int32_t leaf_size,
                              double* energy, double* dE);
+
+/* Work of the last rc_bh_differential: cluster (far-field) interactions and
+ * edge pairs visited in leaves (near field, excluded pairs included), the
+ * number of BVH nodes and levels.  Synchronises the stream. */
+rc_status rc_bh_last_work(rc_ctx* ctx, int64_t* far_pairs, int64_t* near_pairs, int32_t* nodes, int32_t* depth);
 
 /* Exact edge-midpoint energy and differential (the theta -> 0 limit of
  * rc_bh_differential), in the context's dtype. */

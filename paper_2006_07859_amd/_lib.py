@@ -30,8 +30,8 @@ EXPORTED = [
     "rc_default_solve_opts", "rc_default_ls_opts", "rc_last_error", "rc_create", "rc_destroy", "rc_energy",
     "rc_differential", "rc_sobolev_apply", "rc_sobolev_apply_prec", "rc_sobolev_diag", "rc_assemble_dense",
     "rc_set_constraints", "rc_constraint_values", "rc_constraint_count", "rc_project", "rc_sobolev_gradient",
-    "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_midpoint_differential", "rc_profile_enable",
-    "rc_profile_read",
+    "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_bh_last_work", "rc_midpoint_differential",
+    "rc_profile_enable", "rc_profile_read",
 ]
 
 
@@ -98,6 +98,7 @@ def load():
         "rc_step": (I32, [P, P, C.POINTER(SolveOpts), C.POINTER(LsOpts), C.POINTER(Stats)]),
         "rc_bh_differential": (I32, [P, P, D, I32, P, P]),
         "rc_midpoint_differential": (I32, [P, P, P, P]),
+        "rc_bh_last_work": (I32, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(I32), C.POINTER(I32)]),
         "rc_profile_enable": (I32, [P, I32]),
         "rc_profile_read": (I32, [P, I32, C.POINTER(D), C.POINTER(I32)]),
     }
@@ -263,3 +264,8 @@ class Context:
         ms, n = C.c_double(0.0), C.c_int32(0)
         _check(load().rc_profile_read(self.h, int(which), C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def rc_bh_last_work(self):
+        f, n, nodes, depth = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32()
+        _check(load().rc_bh_last_work(self.h, C.byref(f), C.byref(n), C.byref(nodes), C.byref(depth)))
+        return {"far": f.value, "near": n.value, "nodes": nodes.value, "depth": depth.value}

@@ -152,6 +152,7 @@ rc_status rc_destroy(rc_ctx* c) {
   if (!c) return RC_OK;
   hipStreamSynchronize(c->stream);
   c->timer.clear();
+  c->bvh.release();
   mg_free(c);
   dense_free(c->dense);
   cons_free(c->cons);
@@ -391,5 +392,39 @@ extern "C" rc_status rc_profile_read(rc_ctx* c, int32_t which, double* total_ms,
   }
   *total_ms = tot;
   *launches = (int32_t)(v.size() / 2);
+  return RC_OK;
+}
+
+extern "C" rc_status rc_bh_differential(rc_ctx* c, const double* gamma, double theta, int32_t leaf_size,
+                                        double* energy, double* dE) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(check_ptrs({gamma, dE}));
+  if (!(theta > 0.0) || !(theta < 0.5)) {
+    set_error("rc_bh_differential: theta must lie in (0, 0.5) so that a target's own cluster is never admissible");
+    return RC_ERR_ARG;
+  }
+  if (leaf_size < 1 || leaf_size > 256) {
+    set_error("rc_bh_differential: leaf_size must lie in [1, 256]");
+    return RC_ERR_ARG;
+  }
+  RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));
+  return launch_bh(c->curve, c->bvh, c->alpha, c->beta, theta, leaf_size, energy, dE, c->stream);
+}
+
+extern "C" rc_status rc_bh_last_work(rc_ctx* c, int64_t* far_pairs, int64_t* near_pairs, int32_t* nodes,
+                                     int32_t* depth) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(check_ptrs({far_pairs, near_pairs, nodes, depth}));
+  if (!c->bvh.work) {
+    set_error("rc_bh_last_work: no Barnes-Hut evaluation yet");
+    return RC_ERR_ARG;
+  }
+  unsigned long long w[2];
+  RC_HIP(hipMemcpyAsync(w, c->bvh.work, sizeof(w), hipMemcpyDeviceToHost, c->stream));
+  RC_HIP(hipStreamSynchronize(c->stream));
+  *far_pairs = (int64_t)w[0];
+  *near_pairs = (int64_t)w[1];
+  *nodes = c->bvh.n_nodes;
+  *depth = c->bvh.depth;
   return RC_OK;
 }

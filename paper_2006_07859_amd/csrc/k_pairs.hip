@@ -19,73 +19,10 @@
 
 #include <type_traits>
 
+#include "pair_math.h"
 #include "rc_internal.h"
 
 namespace rc {
-
-// ---------------------------------------------------------------------------
-// math helpers: hardware transcendentals in FP32, library ones in FP64
-// ---------------------------------------------------------------------------
-template <typename R> __device__ __forceinline__ R f_rsq(R x);
-template <> __device__ __forceinline__ float f_rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-template <> __device__ __forceinline__ double f_rsq<double>(double x) { return rsqrt(x); }
-template <typename R> __device__ __forceinline__ R f_sqrt(R x);
-template <> __device__ __forceinline__ float f_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
-template <> __device__ __forceinline__ double f_sqrt<double>(double x) { return sqrt(x); }
-template <typename R> __device__ __forceinline__ R f_exp2(R x);
-template <> __device__ __forceinline__ float f_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
-template <> __device__ __forceinline__ double f_exp2<double>(double x) { return exp2(x); }
-template <typename R> __device__ __forceinline__ R f_log2(R x);
-template <> __device__ __forceinline__ float f_log2<float>(float x) { return __builtin_amdgcn_logf(x); }
-template <> __device__ __forceinline__ double f_log2<double>(double x) { return log2(x); }
-
-// r2^(-beta/2) from rs = 1/sqrt(r2) and ri = 1/r2.
-template <int EC, typename R>
-__device__ __forceinline__ R pow_beta(R r2, R rs, R ri, R half_beta) {
-  if constexpr (EC == kA2B4) return ri * ri;
-  else if constexpr (EC == kA2B45) return ri * ri * f_sqrt<R>(rs);
-  else if constexpr (EC == kA3B6) return ri * ri * ri;
-  else return f_exp2<R>(-half_beta * f_log2<R>(r2));
-}
-
-// ca = c^(alpha/2) and f = (alpha/2) c^(alpha/2 - 1) for c = |T x d|^2 >= 0.
-template <int EC, typename R>
-__device__ __forceinline__ void pow_alpha(R c, R half_alpha, R& ca, R& f) {
-  if constexpr (EC == kA2B4 || EC == kA2B45) {
-    ca = c;
-    f = R(1);
-  } else if constexpr (EC == kA3B6) {
-    R sq = f_sqrt<R>(c);
-    ca = c * sq;
-    f = R(1.5) * sq;
-  } else {
-    if (c > R(0)) {
-      ca = f_exp2<R>(half_alpha * f_log2<R>(c));
-      f = half_alpha * ca / c;
-    } else {
-      ca = R(0);
-      f = R(0);
-    }
-  }
-}
-
-// r2^(-(2 sigma + 1)/2): the weight exponent of B and B0 (Sec. 4.2.2-4.2.3).
-template <int EC, typename R>
-__device__ __forceinline__ R pow_sigma(R r2, R rs, R ri, R half_expo) {
-  if constexpr (EC == kA2B4) return ri;                       // 2 sigma + 1 = 2
-  else if constexpr (EC == kA2B45) return ri * f_sqrt<R>(rs);  // 2.5
-  else return f_exp2<R>(-half_expo * f_log2<R>(r2));          // 7/3 for (3,6), general
-}
-
-template <typename R>
-__device__ __forceinline__ R cross_norm2(R tx, R ty, R tz, R dx, R dy, R dz) {
-  // |T x d|^2 from the cross product itself: accurate when d is nearly
-  // parallel to T, where |d|^2 - (T.d)^2 would cancel catastrophically.
-  R cx = ty * dz - tz * dy;
-  R cy = tz * dx - tx * dz;
-  R cz = tx * dy - ty * dx;
-  return cx * cx + cy * cy + cz * cz;
-}
 
 ExpCase exp_case(double alpha, double beta) {
   if (alpha == 2.0 && beta == 4.0) return kA2B4;
@@ -111,65 +48,6 @@ __global__ void k_geometry(const double* __restrict__ gamma, const int2* __restr
   A[I] = V4<R>{R(p0), R(p1), R(p2), R(l)};
   B[I] = V4<R>{R(q0), R(q1), R(q2), R(0)};
   T[I] = V4<R>{R(d0 * il), R(d1 * il), R(d2 * il), R(0)};
-}
-
-// ---------------------------------------------------------------------------
-// energy and differential, trapezoid rule over the four vertex pairs
-// ---------------------------------------------------------------------------
-// Accumulator slots (per target edge I; every term carries w = l_J / 4):
-//  0 E    sum k(d, T_I)                                  -> energy l_I * E
-//  1 S    sum k(d, T_I) + k(d, T_J)                      -> dl_I term
-//  2-4 G1 sum over (i1, j_b) of grad_d[k_I + k_J] minus its T_I part
-//  5-7 G2 same for i2
-//  8 Gt1, 9 Gt2: coefficient of T_I in those gradients
-//  10-12 Hd, 13 Ht: dk/dT_I projected on the tangent plane = -2 (Hd - Ht T_I)
-template <typename R, int EC, bool GRAD>
-struct TpeAcc {
-  R v[GRAD ? kTpeSlots : 1];
-};
-
-template <typename R, int EC, bool GRAD>
-__device__ __forceinline__ void tpe_vertex_pair(
-    R px, R py, R pz, R tIx, R tIy, R tIz,                // target vertex, T_I
-    R qx, R qy, R qz, R tJx, R tJy, R tJz,                // source vertex, T_J
-    bool same, R w, R half_alpha, R half_beta, R beta,
-    R& E, R& S, R& Gx, R& Gy, R& Gz, R& Gt, R& Hx, R& Hy, R& Hz, R& Ht) {
-  R dx = px - qx, dy = py - qy, dz = pz - qz;
-  R r2 = dx * dx + dy * dy + dz * dz;
-  r2 = same ? R(1) : r2;
-  R rs = f_rsq<R>(r2);
-  R ri = rs * rs;
-  R rbw = pow_beta<EC, R>(r2, rs, ri, half_beta) * w;
-  R cI = cross_norm2<R>(tIx, tIy, tIz, dx, dy, dz);
-  R caI, fI;
-  pow_alpha<EC, R>(cI, half_alpha, caI, fI);
-  R kI = caI * rbw;
-  E += kI;
-  if constexpr (GRAD) {
-    R cJ = cross_norm2<R>(tJx, tJy, tJz, dx, dy, dz);
-    R caJ, fJ;
-    pow_alpha<EC, R>(cJ, half_alpha, caJ, fJ);
-    R kJ = caJ * rbw;
-    R ks = kI + kJ;
-    S += ks;
-    R tI = tIx * dx + tIy * dy + tIz * dz;
-    R tJ = tJx * dx + tJy * dy + tJz * dz;
-    R gI = R(2) * fI * rbw;
-    R gJ = R(2) * fJ * rbw;
-    // grad_d k = 2 f rb (d - t T) - beta k d / r2
-    R c1 = gI + gJ - beta * ks * ri;
-    R c2 = gJ * tJ;
-    Gx += c1 * dx - c2 * tJx;
-    Gy += c1 * dy - c2 * tJy;
-    Gz += c1 * dz - c2 * tJz;
-    Gt += gI * tI;
-    // dk/dT_I on the tangent plane: -2 f rb t (d - t T_I)
-    R c3 = fI * rbw * tI;
-    Hx += c3 * dx;
-    Hy += c3 * dy;
-    Hz += c3 * dz;
-    Ht += c3 * tI;
-  }
 }
 
 // Chain-near test: edges of the same chain at most kBand apart (cyclically on loops).
@@ -577,13 +455,14 @@ __global__ void k_gather_sob(const double* __restrict__ edge_out, const int* __r
 //  minus its T_I part, 5 Gt; 6-8 Hd, 9 Ht as in the trapezoid kernel.
 constexpr int kMidSlotsUsed = 10;
 
-template <typename R, int EC>
+template <typename R, int EC, bool BAND>
 __global__ __launch_bounds__(kTile) void k_mid_pairs(
     const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB, const V4<R>* __restrict__ GT,
-    const int2* __restrict__ edges, int nE, int src_per_chunk, R half_alpha, R half_beta, R beta,
-    double* __restrict__ part) {
+    const int2* __restrict__ edges, const int4* __restrict__ cinfo, int nE, int src_per_chunk, R half_alpha,
+    R half_beta, R beta, double* __restrict__ part) {
   __shared__ V4<R> sX[kTile], sT[kTile];
   __shared__ int2 sE[kTile];
+  __shared__ int4 sC[BAND ? kTile : 1];
   const int tid = threadIdx.x;
   const int I = blockIdx.x * kTile + tid;
   const bool act = I < nE;
@@ -591,6 +470,8 @@ __global__ __launch_bounds__(kTile) void k_mid_pairs(
   const V4<R> a = GA[Ic], b = GB[Ic], t = GT[Ic];
   const R mx = R(0.5) * (a.x + b.x), my = R(0.5) * (a.y + b.y), mz = R(0.5) * (a.z + b.z);
   const int2 ei = act ? edges[Ic] : make_int2(-1, -2);
+  int4 ci = make_int4(-1, 0, 0, 0);
+  if constexpr (BAND) ci = act ? cinfo[Ic] : make_int4(-1, 0, 0, 0);
   double acc[kMidSlotsUsed];
 #pragma unroll
   for (int k = 0; k < kMidSlotsUsed; ++k) acc[k] = 0.0;
@@ -604,6 +485,7 @@ __global__ __launch_bounds__(kTile) void k_mid_pairs(
       sX[tid] = V4<R>{R(0.5) * (ga.x + gb.x), R(0.5) * (ga.y + gb.y), R(0.5) * (ga.z + gb.z), ga.w};
       sT[tid] = GT[j];
       sE[tid] = edges[j];
+      if constexpr (BAND) sC[tid] = cinfo[j];
     }
     __syncthreads();
     const int cnt = min(kTile, s1 - t0);
@@ -612,12 +494,16 @@ __global__ __launch_bounds__(kTile) void k_mid_pairs(
       R E = 0, S = 0, Gx = 0, Gy = 0, Gz = 0, Gt = 0, Hx = 0, Hy = 0, Hz = 0, Ht = 0;
       for (int u = u0; u < u1; ++u) {
         const V4<R> q = sX[u], qt = sT[u];
-        const int2 ej = sE[u];
-        const bool excl = (ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y);
-        const R w = excl ? R(0) : q.w;
-        tpe_vertex_pair<R, EC, true>(mx, my, mz, t.x, t.y, t.z, q.x, q.y, q.z, qt.x, qt.y, qt.z,
-                                     ei.x == ej.x && ei.y == ej.y, w, half_alpha, half_beta, beta,
-                                     E, S, Gx, Gy, Gz, Gt, Hx, Hy, Hz, Ht);
+        bool skip;
+        if constexpr (BAND) {
+          skip = chain_near(ci, sC[u]);
+        } else {
+          const int2 ej = sE[u];
+          skip = (ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y);
+        }
+        const R w = skip ? R(0) : q.w;
+        tpe_vertex_pair<R, EC, true>(mx, my, mz, t.x, t.y, t.z, q.x, q.y, q.z, qt.x, qt.y, qt.z, skip, w, half_alpha,
+                                     half_beta, beta, E, S, Gx, Gy, Gz, Gt, Hx, Hy, Hz, Ht);
       }
       acc[0] += (double)E; acc[1] += (double)S; acc[2] += (double)Gx; acc[3] += (double)Gy;
       acc[4] += (double)Gz; acc[5] += (double)Gt; acc[6] += (double)Hx; acc[7] += (double)Hy;
@@ -629,6 +515,45 @@ __global__ __launch_bounds__(kTile) void k_mid_pairs(
 #pragma unroll
     for (int k = 0; k < kMidSlotsUsed; ++k) out[(size_t)k * nE] = acc[k];
   }
+}
+
+// FP64 near band of the edge-midpoint sum (the pairs the BAND kernel skips).
+template <int EC>
+__global__ void k_mid_band(const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB,
+                           const V4<double>* __restrict__ GT, const int2* __restrict__ edges,
+                           const int4* __restrict__ cinfo, const int* __restrict__ chain_edge, int nE,
+                           double half_alpha, double half_beta, double beta, int chunk, double* __restrict__ part) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nE) return;
+  const V4<double> a = GA[I], b = GB[I], t = GT[I];
+  const double mx = 0.5 * (a.x + b.x), my = 0.5 * (a.y + b.y), mz = 0.5 * (a.z + b.z);
+  const int2 ei = edges[I];
+  const int4 ci = cinfo[I];
+  const int m = ci.z;
+  int q0, q1;
+  if (ci.w && m <= 2 * kBand + 1) {
+    q0 = 0;
+    q1 = m - 1;
+  } else if (ci.w) {
+    q0 = ci.y - kBand;
+    q1 = ci.y + kBand;
+  } else {
+    q0 = max(0, ci.y - kBand);
+    q1 = min(m - 1, ci.y + kBand);
+  }
+  double E = 0, S = 0, Gx = 0, Gy = 0, Gz = 0, Gt = 0, Hx = 0, Hy = 0, Hz = 0, Ht = 0;
+  for (int q = q0; q <= q1; ++q) {
+    const int J = chain_edge[ci.x + ((q % m) + m) % m];
+    const int2 ej = edges[J];
+    if ((ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y)) continue;
+    const V4<double> qa = GA[J], qb = GB[J], qt = GT[J];
+    tpe_vertex_pair<double, EC, true>(mx, my, mz, t.x, t.y, t.z, 0.5 * (qa.x + qb.x), 0.5 * (qa.y + qb.y),
+                                      0.5 * (qa.z + qb.z), qt.x, qt.y, qt.z, false, qa.w, half_alpha, half_beta, beta,
+                                      E, S, Gx, Gy, Gz, Gt, Hx, Hy, Hz, Ht);
+  }
+  const double v[kMidSlotsUsed] = {E, S, Gx, Gy, Gz, Gt, Hx, Hy, Hz, Ht};
+  double* out = part + (size_t)chunk * kMidSlotsUsed * nE + I;
+  for (int k = 0; k < kMidSlotsUsed; ++k) out[(size_t)k * nE] = v[k];
 }
 
 __global__ void k_mid_finalize(const double* __restrict__ part, int nchunk, int nE,
@@ -842,9 +767,17 @@ rc_status launch_sobolev(const Curve& c, double alpha, double beta, rc_dtype pre
 template <typename R>
 static void dispatch_mid(const Curve& c, const EdgeGeom<R>& g, double alpha, double beta, hipStream_t s) {
   dim3 grid(cdiv(c.nE, kTile), c.nchunk);
-#define RC_MID(EC)                                                                                   \
-  hipLaunchKernelGGL((k_mid_pairs<R, EC>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, c.nE,     \
-                     c.src_per_chunk, R(0.5 * alpha), R(0.5 * beta), R(beta), c.part)
+  const bool band = std::is_same<R, float>::value && c.chain;
+#define RC_MID(EC)                                                                                             \
+  if (band) {                                                                                                  \
+    hipLaunchKernelGGL((k_mid_pairs<R, EC, true>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, c.cinfo,   \
+                       c.nE, c.src_per_chunk, R(0.5 * alpha), R(0.5 * beta), R(beta), c.part);                 \
+    hipLaunchKernelGGL((k_mid_band<EC>), dim3(cdiv(c.nE, 64)), dim3(64), 0, s, c.gd.a, c.gd.b, c.gd.t, c.edges, \
+                       c.cinfo, c.chain_edge, c.nE, 0.5 * alpha, 0.5 * beta, beta, c.nchunk, c.part);          \
+  } else {                                                                                                     \
+    hipLaunchKernelGGL((k_mid_pairs<R, EC, false>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, c.cinfo,  \
+                       c.nE, c.src_per_chunk, R(0.5 * alpha), R(0.5 * beta), R(beta), c.part);                 \
+  }
   switch (exp_case(alpha, beta)) {
     case kA2B4: RC_MID(kA2B4); break;
     case kA2B45: RC_MID(kA2B45); break;
@@ -859,7 +792,11 @@ rc_status launch_midpoint(const Curve& c, double alpha, double beta, rc_dtype pr
   if (prec == RC_F32) dispatch_mid<float>(c, c.gf, alpha, beta, s);
   else dispatch_mid<double>(c, c.gd, alpha, beta, s);
   RC_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_mid_finalize, dim3(cdiv(c.nE, 256)), dim3(256), 0, s, c.part, c.nchunk, c.nE,
+  return finalize_midpoint(c, c.nchunk + ((prec == RC_F32 && c.chain) ? 1 : 0), energy, dE, s);
+}
+
+rc_status finalize_midpoint(const Curve& c, int nparts, double* energy, double* dE, hipStream_t s) {
+  hipLaunchKernelGGL(k_mid_finalize, dim3(cdiv(c.nE, 256)), dim3(256), 0, s, c.part, nparts, c.nE,
                      (const double*)c.gd.a, (const double*)c.gd.t, c.edge_out);
   if (dE)
     hipLaunchKernelGGL(k_gather_vertex, dim3(cdiv(c.nV, 256)), dim3(256), 0, s, c.edge_out, c.inc_off,

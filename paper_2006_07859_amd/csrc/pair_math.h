@@ -1,0 +1,130 @@
+// Device math shared by the pair kernels and the Barnes-Hut traversal:
+// transcendental helpers, exponent specialisations and the per-vertex-pair
+// accumulation of the tangent-point energy and its derivatives.
+#pragma once
+
+#include "rc_internal.h"
+
+namespace rc {
+
+// ---------------------------------------------------------------------------
+// math helpers: hardware transcendentals in FP32, library ones in FP64
+// ---------------------------------------------------------------------------
+template <typename R> __device__ __forceinline__ R f_rsq(R x);
+template <> __device__ __forceinline__ float f_rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ __forceinline__ double f_rsq<double>(double x) { return rsqrt(x); }
+template <typename R> __device__ __forceinline__ R f_sqrt(R x);
+template <> __device__ __forceinline__ float f_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> __device__ __forceinline__ double f_sqrt<double>(double x) { return sqrt(x); }
+template <typename R> __device__ __forceinline__ R f_exp2(R x);
+template <> __device__ __forceinline__ float f_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
+template <> __device__ __forceinline__ double f_exp2<double>(double x) { return exp2(x); }
+template <typename R> __device__ __forceinline__ R f_log2(R x);
+template <> __device__ __forceinline__ float f_log2<float>(float x) { return __builtin_amdgcn_logf(x); }
+template <> __device__ __forceinline__ double f_log2<double>(double x) { return log2(x); }
+
+// r2^(-beta/2) from rs = 1/sqrt(r2) and ri = 1/r2.
+template <int EC, typename R>
+__device__ __forceinline__ R pow_beta(R r2, R rs, R ri, R half_beta) {
+  if constexpr (EC == kA2B4) return ri * ri;
+  else if constexpr (EC == kA2B45) return ri * ri * f_sqrt<R>(rs);
+  else if constexpr (EC == kA3B6) return ri * ri * ri;
+  else return f_exp2<R>(-half_beta * f_log2<R>(r2));
+}
+
+// ca = c^(alpha/2) and f = (alpha/2) c^(alpha/2 - 1) for c = |T x d|^2 >= 0.
+template <int EC, typename R>
+__device__ __forceinline__ void pow_alpha(R c, R half_alpha, R& ca, R& f) {
+  if constexpr (EC == kA2B4 || EC == kA2B45) {
+    ca = c;
+    f = R(1);
+  } else if constexpr (EC == kA3B6) {
+    R sq = f_sqrt<R>(c);
+    ca = c * sq;
+    f = R(1.5) * sq;
+  } else {
+    if (c > R(0)) {
+      ca = f_exp2<R>(half_alpha * f_log2<R>(c));
+      f = half_alpha * ca / c;
+    } else {
+      ca = R(0);
+      f = R(0);
+    }
+  }
+}
+
+// r2^(-(2 sigma + 1)/2): the weight exponent of B and B0 (Sec. 4.2.2-4.2.3).
+template <int EC, typename R>
+__device__ __forceinline__ R pow_sigma(R r2, R rs, R ri, R half_expo) {
+  if constexpr (EC == kA2B4) return ri;                       // 2 sigma + 1 = 2
+  else if constexpr (EC == kA2B45) return ri * f_sqrt<R>(rs);  // 2.5
+  else return f_exp2<R>(-half_expo * f_log2<R>(r2));          // 7/3 for (3,6), general
+}
+
+template <typename R>
+__device__ __forceinline__ R cross_norm2(R tx, R ty, R tz, R dx, R dy, R dz) {
+  // |T x d|^2 from the cross product itself: accurate when d is nearly
+  // parallel to T, where |d|^2 - (T.d)^2 would cancel catastrophically.
+  R cx = ty * dz - tz * dy;
+  R cy = tz * dx - tx * dz;
+  R cz = tx * dy - ty * dx;
+  return cx * cx + cy * cy + cz * cz;
+}
+
+// ---------------------------------------------------------------------------
+// energy and differential, trapezoid rule over the four vertex pairs
+// ---------------------------------------------------------------------------
+// Accumulator slots (per target edge I; every term carries w = l_J / 4):
+//  0 E    sum k(d, T_I)                                  -> energy l_I * E
+//  1 S    sum k(d, T_I) + k(d, T_J)                      -> dl_I term
+//  2-4 G1 sum over (i1, j_b) of grad_d[k_I + k_J] minus its T_I part
+//  5-7 G2 same for i2
+//  8 Gt1, 9 Gt2: coefficient of T_I in those gradients
+//  10-12 Hd, 13 Ht: dk/dT_I projected on the tangent plane = -2 (Hd - Ht T_I)
+// tjj = |T_J|^2: 1 for an edge; a Barnes-Hut cluster's length-weighted mean
+// tangent is shorter, and d|T x d|^2/dd = 2 (|T|^2 d - (T.d) T).
+template <typename R, int EC, bool GRAD>
+__device__ __forceinline__ void tpe_vertex_pair(
+    R px, R py, R pz, R tIx, R tIy, R tIz,                // target vertex, T_I
+    R qx, R qy, R qz, R tJx, R tJy, R tJz,                // source vertex, T_J
+    bool same, R w, R half_alpha, R half_beta, R beta,
+    R& E, R& S, R& Gx, R& Gy, R& Gz, R& Gt, R& Hx, R& Hy, R& Hz, R& Ht, R tjj = R(1)) {
+  R dx = px - qx, dy = py - qy, dz = pz - qz;
+  R r2 = dx * dx + dy * dy + dz * dz;
+  r2 = same ? R(1) : r2;
+  R rs = f_rsq<R>(r2);
+  R ri = rs * rs;
+  R rbw = pow_beta<EC, R>(r2, rs, ri, half_beta) * w;
+  R cI = cross_norm2<R>(tIx, tIy, tIz, dx, dy, dz);
+  R caI, fI;
+  pow_alpha<EC, R>(cI, half_alpha, caI, fI);
+  R kI = caI * rbw;
+  E += kI;
+  if constexpr (GRAD) {
+    R cJ = cross_norm2<R>(tJx, tJy, tJz, dx, dy, dz);
+    R caJ, fJ;
+    pow_alpha<EC, R>(cJ, half_alpha, caJ, fJ);
+    R kJ = caJ * rbw;
+    R ks = kI + kJ;
+    S += ks;
+    R tI = tIx * dx + tIy * dy + tIz * dz;
+    R tJ = tJx * dx + tJy * dy + tJz * dz;
+    R gI = R(2) * fI * rbw;
+    R gJ = R(2) * fJ * rbw;
+    // grad_d k = 2 f rb (d - t T) - beta k d / r2
+    R c1 = gI + gJ * tjj - beta * ks * ri;
+    R c2 = gJ * tJ;
+    Gx += c1 * dx - c2 * tJx;
+    Gy += c1 * dy - c2 * tJy;
+    Gz += c1 * dz - c2 * tJz;
+    Gt += gI * tI;
+    // dk/dT_I on the tangent plane: -2 f rb t (d - t T_I)
+    R c3 = fI * rbw * tI;
+    Hx += c3 * dx;
+    Hy += c3 * dy;
+    Hz += c3 * dz;
+    Ht += c3 * tI;
+  }
+}
+
+}  // namespace rc

@@ -141,6 +141,26 @@ rc_status launch_sobolev(const Curve& c, double alpha, double beta, rc_dtype pre
 // Exact edge-midpoint energy and differential.
 rc_status launch_midpoint(const Curve& c, double alpha, double beta, rc_dtype prec,
                           double* energy, double* dE, hipStream_t s);
+// Shared tail of the edge-midpoint kernels: sums nparts chunks of the
+// 10-slot partials, writes energy and dE.
+rc_status finalize_midpoint(const Curve& c, int nparts, double* energy, double* dE, hipStream_t s);
+
+// Device BVH over tangent-points for Barnes-Hut (k_bvh.hip).
+struct Bvh {
+  int nE = 0, cap = 0, n_nodes = 0, depth = 0;
+  int *perm = nullptr, *scratch = nullptr, *split = nullptr, *counter = nullptr;
+  float* pts = nullptr;
+  int4* node = nullptr;
+  float4 *na = nullptr, *nb = nullptr;
+  float2* nr = nullptr;
+  unsigned long long* work = nullptr;  // far-field and near-field interaction counts of the last traversal
+  rc_status ensure(int nE_);
+  void release();
+};
+// Barnes-Hut energy and differential in FP32 (needs the FP32 geometry).
+rc_status launch_bh(const Curve& c, Bvh& bvh, double alpha, double beta, double theta, int leaf, double* energy,
+                    double* dE, hipStream_t s);
+
 // Dense FP64 A (row-major nV x nV); needs degree <= 2.
 rc_status launch_assemble_dense(const Curve& c, double alpha, double beta, double* A,
                                 hipStream_t s);

@@ -75,6 +75,7 @@ struct rc_ctx {
   int mg_min = 0, cheb_deg = 0;
   // dense direct path on the finest level
   rc::Dense dense;
+  rc::Bvh bvh;
   rc::KernelTimer timer;
 };
 
