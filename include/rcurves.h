@@ -77,6 +77,18 @@ typedef struct {
   int32_t mg_min_vertices; /* coarsest multigrid level size (vertices per loop, total) */
   int32_t cheb_degree;   /* Chebyshev smoothing steps per V-cycle visit */
   int32_t op_f64;        /* 1 = the PCG operator runs in FP64 even when dtype is F32 */
+  int32_t lowp;          /* precision path (see rc_lowp_assemble): 0 = off; 1 = BF16, 2 = FP16
+                            assembled blocks in the multigrid smoothers of the finest levels, the
+                            Krylov recurrence on the operator chosen by lowp_outer, and the FP64
+                            matrix-free operator for the true residuals (iterative refinement) */
+  int32_t lowp_band;     /* FP32 band half-width along the chains, 0..64 */
+  int32_t lowp_min_vertices; /* smoothed multigrid levels with at least this many vertices use their
+                                own 16-bit block (the finest level always does when lowp != 0) */
+  int32_t lowp_outer;    /* Krylov operator of the precision path: 0 = the matrix-free operator
+                            (FP64 when op_f64 != 0, else the context precision), 1 = the assembled
+                            FP32 block, refined by the FP64 true residuals (inner_tol) */
+  double inner_tol;      /* refinement sweep: restart from the FP64 true residual once the recurrence
+                            residual has dropped by this factor (0 = only at tol) */
 } rc_solve_opts;
 
 typedef struct {
@@ -101,7 +113,7 @@ typedef struct {
   int32_t backtracks;
   int32_t proj_iters;    /* projection iterations at the accepted step */
   int32_t status;        /* rc_status of the last call */
-  int32_t pad;
+  int32_t sweeps;        /* FP64 true-residual evaluations of the gradient solve (refinement sweeps) */
   double t_eval_ms;      /* rc_step: energy + differential phase (HIP events) */
   double t_solve_ms;     /* rc_step: constraint/multigrid setup + gradient solve */
   double t_search_ms;    /* rc_step: line search with projection */
@@ -215,12 +227,40 @@ rc_status rc_bh_last_work(rc_ctx* ctx, int64_t* far_pairs, int64_t* near_pairs, 
  * rc_bh_differential), in the context's dtype. */
 rc_status rc_midpoint_differential(rc_ctx* ctx, const double* gamma, double* energy, double* dE);
 
+/* Precision path: the Sobolev block A = B + B0 (Sec. 4.2.2-4.2.3, the entries of
+ * the dense matrix the increments of those sections assemble) stored in 16 bits.
+ * S = D^-1/2 A D^-1/2 with D = diag(A) from FP64 per-edge sums; off-diagonal
+ * entries of S more than `band` steps apart along a chain are computed in FP32
+ * and rounded to BF16 (fmt 1) or FP16 (fmt 2); those within the band are
+ * computed in FP64 and kept in FP32; the diagonal is recomputed in FP64 as
+ * minus the row sums of the stored values, so the stored operator
+ * A^ = D^1/2 (S^_off + diag sigma) D^1/2 maps constants to zero.
+ * With with_f32 != 0 the same pass also keeps every entry of S in FP32 (the
+ * non-band ones as evaluated in FP32), with its own recomputed diagonal.
+ * gamma: device double [nV][3].  fmt: 1 or 2 (else RC_ERR_ARG); band: 0..64
+ * (else RC_ERR_ARG).  Needs every vertex of degree <= 2 (RC_ERR_UNSUPPORTED).
+ * The context owns the blocks (about nV^2 * 2 bytes, plus nV^2 * 4 with
+ * with_f32, of device memory) and replaces them on the next call; the
+ * solver's precision option reassembles them at the curve being solved.
+ * RC_ERR_NOMEM when they do not fit. */
+rc_status rc_lowp_assemble(rc_ctx* ctx, const double* gamma, int32_t fmt, int32_t band, int32_t with_f32);
+
+/* Y = A^ X with the last assembled block.  f32 = 0: the 16-bit block, with
+ * X' = D^1/2 X scaled by a power of two and split into hi + lo 16-bit parts,
+ * MFMA products with FP32 accumulation; f32 = 1: the FP32 block (FP32 MFMA).
+ * Band and diagonal terms and the final D^1/2 scaling in FP64.
+ * X, Y: device double [nV][3]; Y is overwritten.  RC_ERR_ARG if that block
+ * has not been assembled. */
+rc_status rc_lowp_apply(rc_ctx* ctx, const double* X, double* Y, int32_t f32);
+
 /* Kernel timing with HIP events on the context's stream.  rc_profile_enable
  * clears earlier records and, when enable != 0, brackets every launch of the
  * FP32/FP64 pair kernels with a pair of events.  rc_profile_read synchronises
  * the stream and returns the summed duration (ms) and the launch count of
  * which = 0: the energy + differential pair kernel, 1: the FP32 operator pair
- * kernel on the finest level (coarse multigrid levels are not timed). */
+ * kernel on the finest level (coarse multigrid levels are not timed), 2: the
+ * 16-bit assembled product kernel on the finest level, 3: the FP32 assembled
+ * product kernel. */
 rc_status rc_profile_enable(rc_ctx* ctx, int32_t enable);
 rc_status rc_profile_read(rc_ctx* ctx, int32_t which, double* total_ms, int32_t* launches);
 

@@ -31,7 +31,7 @@ EXPORTED = [
     "rc_differential", "rc_sobolev_apply", "rc_sobolev_apply_prec", "rc_sobolev_diag", "rc_assemble_dense",
     "rc_set_constraints", "rc_constraint_values", "rc_constraint_count", "rc_project", "rc_sobolev_gradient",
     "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_bh_last_work", "rc_midpoint_differential",
-    "rc_profile_enable", "rc_profile_read",
+    "rc_profile_enable", "rc_profile_read", "rc_lowp_assemble", "rc_lowp_apply",
 ]
 
 
@@ -44,7 +44,8 @@ class RcError(RuntimeError):
 class SolveOpts(C.Structure):
     _fields_ = [("solver", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("replace_every", C.c_int32), ("mg_min_vertices", C.c_int32), ("cheb_degree", C.c_int32),
-                ("op_f64", C.c_int32)]
+                ("op_f64", C.c_int32), ("lowp", C.c_int32), ("lowp_band", C.c_int32),
+                ("lowp_min_vertices", C.c_int32), ("lowp_outer", C.c_int32), ("inner_tol", C.c_double)]
 
 
 class LsOpts(C.Structure):
@@ -57,11 +58,11 @@ class Stats(C.Structure):
     _fields_ = [("energy", C.c_double), ("energy_new", C.c_double), ("grad_norm", C.c_double),
                 ("residual", C.c_double), ("tau", C.c_double), ("iterations", C.c_int32),
                 ("proj_solve_iterations", C.c_int32), ("backtracks", C.c_int32), ("proj_iters", C.c_int32),
-                ("status", C.c_int32), ("pad", C.c_int32), ("t_eval_ms", C.c_double), ("t_solve_ms", C.c_double),
+                ("status", C.c_int32), ("sweeps", C.c_int32), ("t_eval_ms", C.c_double), ("t_solve_ms", C.c_double),
                 ("t_search_ms", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -101,6 +102,8 @@ def load():
         "rc_bh_last_work": (I32, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(I32), C.POINTER(I32)]),
         "rc_profile_enable": (I32, [P, I32]),
         "rc_profile_read": (I32, [P, I32, C.POINTER(D), C.POINTER(I32)]),
+        "rc_lowp_assemble": (I32, [P, P, I32, I32, I32]),
+        "rc_lowp_apply": (I32, [P, P, P, I32]),
     }
     for name, (res, args) in sig.items():
         if not hasattr(lib, name):
@@ -264,6 +267,12 @@ class Context:
         ms, n = C.c_double(0.0), C.c_int32(0)
         _check(load().rc_profile_read(self.h, int(which), C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def rc_lowp_assemble(self, gamma, fmt, band, with_f32=False):
+        _check(load().rc_lowp_assemble(self.h, self._v(gamma, "gamma"), int(fmt), int(band), 1 if with_f32 else 0))
+
+    def rc_lowp_apply(self, X, Y, f32=False):
+        _check(load().rc_lowp_apply(self.h, self._v(X, "X"), self._v(Y, "Y"), 1 if f32 else 0))
 
     def rc_bh_last_work(self):
         f, n, nodes, depth = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32()

@@ -62,6 +62,8 @@ rc_solve_opts resolve(const rc_solve_opts* o) {
   if (!(d.tol > 0)) d.tol = 1e-6;
   if (d.mg_min_vertices <= 0) d.mg_min_vertices = 256;
   if (d.cheb_degree <= 0) d.cheb_degree = 2;
+  if (d.lowp_min_vertices <= 0) d.lowp_min_vertices = 1 << 30;  // finest level only
+  if (!(d.inner_tol > 0.0) || !(d.inner_tol < 1.0)) d.inner_tol = 0.0;
   return d;
 }
 
@@ -85,6 +87,11 @@ void rc_default_solve_opts(rc_solve_opts* o) {
   o->mg_min_vertices = 256;
   o->cheb_degree = 2;
   o->op_f64 = 1;
+  o->lowp = 0;
+  o->lowp_band = 16;
+  o->lowp_min_vertices = 4096;
+  o->lowp_outer = 0;
+  o->inner_tol = 0.0;
 }
 
 void rc_default_ls_opts(rc_ls_opts* o) {
@@ -153,6 +160,7 @@ rc_status rc_destroy(rc_ctx* c) {
   hipStreamSynchronize(c->stream);
   c->timer.clear();
   c->bvh.release();
+  c->lowp.release();
   mg_free(c);
   dense_free(c->dense);
   cons_free(c->cons);
@@ -269,6 +277,7 @@ rc_status rc_sobolev_gradient(rc_ctx* c, const double* gamma, const double* dE, 
   if (stats) {
     stats->iterations = iters;
     stats->residual = res;
+    stats->sweeps = c->last_sweeps;
     stats->status = st;
   }
   return st;
@@ -330,6 +339,7 @@ rc_status rc_step(rc_ctx* c, double* gamma, const rc_solve_opts* so, const rc_ls
     st = solve_prepared(c, dEb, gb, o, &iters, &res);
     local.iterations = iters;
     local.residual = res;
+    local.sweeps = c->last_sweeps;
     if (st) break;
     vec_dot(gb, gb, 3 * c->nV, c->red, c->scal, s);
     double gg;
@@ -378,12 +388,14 @@ extern "C" rc_status rc_profile_enable(rc_ctx* c, int32_t enable) {
 extern "C" rc_status rc_profile_read(rc_ctx* c, int32_t which, double* total_ms, int32_t* launches) {
   RC_TRY(check_ctx(c));
   RC_TRY(check_ptrs({total_ms, launches}));
-  if (which != 0 && which != 1) {
-    set_error("rc_profile_read: which must be 0 (energy+differential pairs) or 1 (operator pairs)");
+  if (which < 0 || which > 3) {
+    set_error("rc_profile_read: which must be 0 (energy+differential pairs), 1 (operator pairs), 2 "
+              "(assembled 16-bit product) or 3 (assembled FP32 product)");
     return RC_ERR_ARG;
   }
   RC_HIP(hipStreamSynchronize(c->stream));
-  const std::vector<hipEvent_t>& v = which == 0 ? c->timer.tpe : c->timer.sob;
+  const std::vector<hipEvent_t>& v =
+      which == 0 ? c->timer.tpe : which == 1 ? c->timer.sob : which == 2 ? c->timer.lowp : c->timer.asm32;
   double tot = 0.0;
   for (size_t i = 0; i + 1 < v.size(); i += 2) {
     float ms = 0.f;
@@ -427,4 +439,26 @@ extern "C" rc_status rc_bh_last_work(rc_ctx* c, int64_t* far_pairs, int64_t* nea
   *nodes = c->bvh.n_nodes;
   *depth = c->bvh.depth;
   return RC_OK;
+}
+
+extern "C" rc_status rc_lowp_assemble(rc_ctx* c, const double* gamma, int32_t fmt, int32_t band, int32_t with_f32) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(check_ptrs({gamma}));
+  if (fmt != 1 && fmt != 2) {
+    set_error("rc_lowp_assemble: fmt must be 1 (BF16) or 2 (FP16)");
+    return RC_ERR_ARG;
+  }
+  if (band < 0 || band > kLowpMaxBand) {
+    set_error("rc_lowp_assemble: band must lie in [0, 64]");
+    return RC_ERR_ARG;
+  }
+  RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));
+  return launch_assemble_lowp(c->curve, c->lowp, fmt, band, with_f32 != 0, c->alpha, c->beta, nullptr, c->stream);
+}
+
+extern "C" rc_status rc_lowp_apply(rc_ctx* c, const double* X, double* Y, int32_t f32) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(check_ptrs({X, Y}));
+  if (f32) return launch_lowp_apply32(c->lowp, X, Y, c->stream, &c->timer);
+  return launch_lowp_apply(c->lowp, X, Y, c->stream, &c->timer);
 }

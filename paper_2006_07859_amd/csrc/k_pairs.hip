@@ -819,17 +819,29 @@ __global__ void k_pick_wq_p0(const double* __restrict__ part, int nchunk, int nE
   edge_out[8 * (size_t)I + 1] = p0;
 }
 
+rc_status launch_edge_sums(const Curve& c, double alpha, double beta, rc_dtype prec, hipStream_t s) {
+  dim3 g1(cdiv(c.nE, 256)), b1(256);
+  if (prec == RC_F32) {
+    RC_HIP(hipMemsetAsync(c.rhs_f[0], 0, sizeof(V4<float>) * c.nE, s));
+    RC_HIP(hipMemsetAsync(c.rhs_f[1], 0, sizeof(V4<float>) * c.nE, s));
+    dispatch_sob<float>(c, c.gf, c.rhs_f, alpha, beta, s);
+  } else {
+    RC_HIP(hipMemsetAsync(c.rhs_d[0], 0, sizeof(V4<double>) * c.nE, s));
+    RC_HIP(hipMemsetAsync(c.rhs_d[1], 0, sizeof(V4<double>) * c.nE, s));
+    dispatch_sob<double>(c, c.gd, c.rhs_d, alpha, beta, s);
+  }
+  hipLaunchKernelGGL(k_pick_wq_p0, g1, b1, 0, s, c.part, c.nchunk, c.nE, c.edge_out);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
 rc_status launch_assemble_dense(const Curve& c, double alpha, double beta, double* A, hipStream_t s) {
   if (!c.chain) {
     set_error("dense assembly needs every vertex to have degree <= 2");
     return RC_ERR_UNSUPPORTED;
   }
   // the operator kernel's per-edge sums Wq and P0 do not depend on the input vector
-  dim3 g1(cdiv(c.nE, 256)), b1(256);
-  RC_HIP(hipMemsetAsync(c.rhs_d[0], 0, sizeof(V4<double>) * c.nE, s));
-  RC_HIP(hipMemsetAsync(c.rhs_d[1], 0, sizeof(V4<double>) * c.nE, s));
-  dispatch_sob<double>(c, c.gd, c.rhs_d, alpha, beta, s);
-  hipLaunchKernelGGL(k_pick_wq_p0, g1, b1, 0, s, c.part, c.nchunk, c.nE, c.edge_out);
+  RC_TRY(launch_edge_sums(c, alpha, beta, RC_F64, s));
   const double sigma = (beta - 1.0) / alpha - 1.0;
   const double half_expo = 0.5 * (2.0 * sigma + 1.0);
   dim3 b2(16, 16), g2(cdiv(c.nV, 16), cdiv(c.nV, 16));

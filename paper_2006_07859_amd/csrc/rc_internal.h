@@ -80,7 +80,7 @@ constexpr int kBand = 32;
 // Optional HIP-event timing of the pair kernels (enabled per context).
 struct KernelTimer {
   bool on = false;
-  std::vector<hipEvent_t> tpe, sob;  // start/stop pairs, in launch order
+  std::vector<hipEvent_t> tpe, sob, lowp, asm32;  // start/stop pairs, in launch order
   void mark(std::vector<hipEvent_t>& v, hipStream_t s) {
     if (!on) return;
     hipEvent_t e;
@@ -91,8 +91,12 @@ struct KernelTimer {
   void clear() {
     for (hipEvent_t e : tpe) hipEventDestroy(e);
     for (hipEvent_t e : sob) hipEventDestroy(e);
+    for (hipEvent_t e : lowp) hipEventDestroy(e);
+    for (hipEvent_t e : asm32) hipEventDestroy(e);
     tpe.clear();
     sob.clear();
+    lowp.clear();
+    asm32.clear();
   }
 };
 
@@ -161,9 +165,45 @@ struct Bvh {
 rc_status launch_bh(const Curve& c, Bvh& bvh, double alpha, double beta, double theta, int leaf, double* energy,
                     double* dE, hipStream_t s);
 
+// Per-edge sums Wq, P0 of the operator kernel into edge_out slots 0 and 1
+// (they do not depend on the vector the operator is applied to).
+rc_status launch_edge_sums(const Curve& c, double alpha, double beta, rc_dtype prec, hipStream_t s);
+
 // Dense FP64 A (row-major nV x nV); needs degree <= 2.
 rc_status launch_assemble_dense(const Curve& c, double alpha, double beta, double* A,
                                 hipStream_t s);
+
+// Assembled Sobolev block (k_lowp.hip): Jacobi-scaled off-diagonal tiles in
+// MFMA operand order, rounded to 16 bits (fmt 1 = BF16, 2 = FP16) and
+// optionally also kept in FP32, an FP32 band along the chains and, for each
+// stored version, a diagonal recomputed in FP64 from the stored rows.
+constexpr int kLowpMaxBand = 64;
+struct LowpOp {
+  int n = 0, fmt = 0, band = 0;
+  bool with32 = false;
+  int nrb = 0, nkt = 0, ngroups = 0, nsplit = 1, per = 0;
+  void* tiles = nullptr;        // [nrb][nkt][64 lanes] 16-byte vectors of 8 16-bit values
+  void* tiles32 = nullptr;      // [nrb][nkt][64 lanes] 8 floats
+  double *rowpart = nullptr, *rowpart32 = nullptr, *dvec = nullptr, *sqd = nullptr;
+  double *sigma = nullptr, *sigma32 = nullptr;  // diagonals balancing the tile entries (band excluded)
+  double *bandpart = nullptr, *mx = nullptr, *cref = nullptr;
+  float *pbuf = nullptr, *sqdf = nullptr, *part = nullptr, *band_val = nullptr;
+  int4* vinfo = nullptr;        // per vertex (chain, position, vertex count, is loop)
+  int* band_idx = nullptr;      // [n][2 band]
+  bool ready = false;
+  rc_status ensure(const Curve& c, int fmt_, int band_, bool with32_);
+  void release();
+  size_t tile_bytes() const { return (size_t)nrb * nkt * 1024; }
+};
+// Builds the blocks of the curve's current geometry (FP32 and FP64 copies
+// must be loaded); diag_out (optional, [nV]) receives the diagonal of the
+// 16-bit operator.
+rc_status launch_assemble_lowp(const Curve& c, LowpOp& op, int fmt, int band, bool with32, double alpha,
+                               double beta, double* diag_out, hipStream_t s);
+// Y = A^ X with the 16-bit block (apply) or the FP32 block (apply32); X and Y
+// [nV][3] FP64.  The product kernels are timed when the timer is on.
+rc_status launch_lowp_apply(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer);
+rc_status launch_lowp_apply32(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer);
 
 // ---------------------------------------------------------------------------
 // dense and vector helpers (k_linalg.hip)

@@ -47,6 +47,7 @@ struct Level {
   int2* prolong = nullptr; // fine vertex -> (coarse a, coarse b): value (x_a + x_b) / 2
   int *restr_off = nullptr, *restr_idx = nullptr;  // coarse vertex -> fine vertices that reference it
   double* gamma = nullptr; // the level's vertex positions [nV][3]
+  LowpOp lowp;             // assembled 16-bit operator of the level (precision path)
 };
 
 struct MGLevelState {
@@ -77,6 +78,11 @@ struct rc_ctx {
   rc::Dense dense;
   rc::Bvh bvh;
   rc::KernelTimer timer;
+  // precision path: the finest level's assembled 16-bit operator; levels
+  // 0 .. lowp_levels-1 use their assembled operator in the current solve
+  rc::LowpOp lowp;
+  int lowp_levels = 0, lowp_fmt = 0, lowp_band = 0, lowp_outer = 0;
+  int last_sweeps = 0;  // FP64 true-residual evaluations of the last PCG solve
 };
 
 namespace rc {

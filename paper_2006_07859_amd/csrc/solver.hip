@@ -519,6 +519,7 @@ void mg_free(rc_ctx* c) {
       dfree(L->restr_off);
       dfree(L->restr_idx);
       dfree(L->gamma);
+      L->lowp.release();
     }
   c->levels.clear();
   for (auto& st : c->mg) {
@@ -627,6 +628,16 @@ static rc_status apply_A(rc_ctx* c, const Curve& cv, const double* X, double* Y,
   return launch_sobolev(cv, c->alpha, c->beta, prec, X, Y, nullptr, c->stream);
 }
 
+static LowpOp& level_lowp(rc_ctx* c, int l) { return l == 0 ? c->lowp : c->levels[l]->lowp; }
+
+// The operator of level l inside PCG and the smoothers: the assembled 16-bit
+// block when the precision path covers the level, else the matrix-free
+// operator in the context's precision.
+static rc_status apply_level(rc_ctx* c, int l, const double* X, double* Y) {
+  if (l < c->lowp_levels) return launch_lowp_apply(level_lowp(c, l), X, Y, c->stream, l == 0 ? &c->timer : nullptr);
+  return apply_A(c, level_curve(c, l), X, Y, c->dtype);
+}
+
 static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
   RC_TRY(mg_build(c));
   hipStream_t s = c->stream;
@@ -650,12 +661,16 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
     Cons& K = level_cons(c, l);
     MGLevelState& st = c->mg[l];
     const int n = cv.nV;
-    RC_TRY(launch_sobolev(cv, c->alpha, c->beta, prec, st.pw, st.t, st.diag, s));
+    if (l < c->lowp_levels)
+      RC_TRY(launch_assemble_lowp(cv, level_lowp(c, l), c->lowp_fmt, c->lowp_band, l == 0 && c->lowp_outer == 1,
+                                  c->alpha, c->beta, st.diag, s));
+    else
+      RC_TRY(launch_sobolev(cv, c->alpha, c->beta, prec, st.pw, st.t, st.diag, s));
     // lambda_max of P D^-1 P A P by power iteration, warm-started from the last call's vector
     double nrm = 0.0;
     for (int it = 0; it < 12; ++it) {
       cons_project(c, cv, K, st.pw, st.pw);
-      RC_TRY(launch_sobolev(cv, c->alpha, c->beta, prec, st.pw, st.t, nullptr, s));
+      RC_TRY(apply_level(c, l, st.pw, st.t));
       cons_project(c, cv, K, st.t, st.t);
       vec_scale_diag_inv(st.t, st.diag, st.d, n, s);
       cons_project(c, cv, K, st.d, st.d);
@@ -692,7 +707,7 @@ static rc_status cheb_smooth(rc_ctx* c, int l, double* x, const double* b, bool 
     vec_copy(b, st.r, n3, s);
     hipMemsetAsync(x, 0, sizeof(double) * n3, s);
   } else {
-    RC_TRY(apply_A(c, cv, x, st.r, c->dtype));
+    RC_TRY(apply_level(c, l, x, st.r));
     vec_axpby(1.0, b, -1.0, st.r, n3, s);
     cons_project(c, cv, K, st.r, st.r);
   }
@@ -702,7 +717,7 @@ static rc_status cheb_smooth(rc_ctx* c, int l, double* x, const double* b, bool 
   for (int k = 0; k < deg; ++k) {
     vec_axpby(1.0, st.d, 1.0, x, n3, s);
     if (k == deg - 1) break;
-    RC_TRY(apply_A(c, cv, st.d, st.t, c->dtype));
+    RC_TRY(apply_level(c, l, st.d, st.t));
     cons_project(c, cv, K, st.t, st.t);
     vec_axpby(-1.0, st.t, 1.0, st.r, n3, s);
     const double rn = 1.0 / (2.0 * sigma - rho);
@@ -727,7 +742,7 @@ static rc_status vcycle(rc_ctx* c, int l, const double* b, double* x) {
   MGLevelState& st = c->mg[l];
   const int n3 = 3 * cv.nV;
   RC_TRY(cheb_smooth(c, l, x, b, true));
-  RC_TRY(apply_A(c, cv, x, st.t, c->dtype));
+  RC_TRY(apply_level(c, l, x, st.t));
   vec_axpby(1.0, b, -1.0, st.t, n3, s);  // t = b - A x
   cons_project(c, cv, K, st.t, st.t);
   Level& C = *c->levels[l + 1];
@@ -762,7 +777,9 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
   hipStream_t s = c->stream;
   const int n3 = 3 * c->nV;
   const rc_dtype op = o.op_f64 ? RC_F64 : c->dtype;
+  const bool lowp = c->lowp_levels > 0;
   double *r = c->r, *z = c->z, *p = c->p, *q = c->q;
+  c->last_sweeps = 0;
   cons_project(c, c->curve, c->cons, b, c->tmp2);  // P b
   vec_dot(c->tmp2, c->tmp2, n3, c->red, c->scal, s);
   double bb;
@@ -774,7 +791,7 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
   if (!(bn > 0)) return RC_OK;
   vec_copy(c->tmp2, r, n3, s);
   int it = 0;
-  double res = 1.0;
+  double res = 1.0, res_sweep = 1.0;  // residual at the start of the current sweep
   bool converged = false;
   while (it < o.max_iter && !converged) {
     RC_TRY(precondition(c, o.solver, r, z));
@@ -784,7 +801,8 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
     RC_TRY(fetch(c, c->scal, &rz, 1));
     int since = 0;
     while (it < o.max_iter) {
-      RC_TRY(apply_A(c, c->curve, p, q, op));
+      if (lowp && c->lowp_outer == 1) RC_TRY(launch_lowp_apply32(c->lowp, p, q, s, &c->timer));
+      else RC_TRY(apply_A(c, c->curve, p, q, op));
       cons_project(c, c->curve, c->cons, q, q);
       vec_dot(p, q, n3, c->red, c->scal, s);
       double pq;
@@ -803,7 +821,7 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
       RC_TRY(fetch(c, c->scal, &rr, 1));
       res = std::sqrt(rr) / bn;
       if (trace_on()) fprintf(stderr, "[rc pcg] it %d rec-res %.3e\n", it, res);
-      if (res < o.tol || (o.replace_every > 0 && since >= o.replace_every)) {
+      if (res < std::max(o.tol, o.inner_tol * res_sweep) || (o.replace_every > 0 && since >= o.replace_every)) {
         // FP64 true residual r = P (b - Abar x); restart the recurrence from it
         RC_TRY(apply_A(c, c->curve, x, c->tmp, RC_F64));
         vec_copy(b, r, n3, s);
@@ -812,6 +830,8 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
         vec_dot(r, r, n3, c->red, c->scal, s);
         RC_TRY(fetch(c, c->scal, &rr, 1));
         res = std::sqrt(rr) / bn;
+        res_sweep = res;
+        ++c->last_sweeps;
         if (trace_on()) fprintf(stderr, "[rc pcg] it %d TRUE-res %.3e\n", it, res);
         if (res < o.tol) converged = true;
         break;
@@ -838,17 +858,50 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
 // entry points used by the C ABI
 // ---------------------------------------------------------------------------
 rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o) {
+  if (o.lowp < 0 || o.lowp > 2) {
+    set_error("solve options: lowp must be 0 (off), 1 (BF16) or 2 (FP16)");
+    return RC_ERR_ARG;
+  }
+  if (o.lowp_outer < 0 || o.lowp_outer > 1) {
+    set_error("solve options: lowp_outer must be 0 (matrix-free) or 1 (assembled FP32)");
+    return RC_ERR_ARG;
+  }
+  c->lowp_levels = 0;
   RC_TRY(load_geometry(c, gamma));
   RC_TRY(cons_prepare(c, c->curve, c->cons, gamma));
   if (o.solver == RC_SOLVE_DENSE) return dense_prepare(c, c->curve, c->cons, c->dense, gamma);
+  c->lowp_fmt = o.lowp;
+  c->lowp_band = o.lowp_band;
+  c->lowp_outer = o.lowp_outer;
   if (o.solver == RC_SOLVE_PCG_MG) {
     if (c->mg_min != o.mg_min_vertices) {
       mg_free(c);
       c->mg_min = o.mg_min_vertices;
     }
     c->cheb_deg = o.cheb_degree;
+    RC_TRY(mg_build(c));
+    // the precision path covers the finest level and every smoothed level
+    // with at least lowp_min_vertices vertices
+    const int nl = (int)c->levels.size();
+    int nlow = 0;
+    if (o.lowp) {
+      nlow = 1;
+      while (nlow < nl - 1 && level_curve(c, nlow).nV >= o.lowp_min_vertices) ++nlow;
+    }
+    c->lowp_levels = nlow;
     RC_TRY(mg_prepare(c, gamma));
-    return load_geometry(c, gamma);
+    RC_TRY(load_geometry(c, gamma));
+    // a single-level hierarchy has no smoothed level: assemble the finest block here
+    if (o.lowp && nl == 1)
+      RC_TRY(launch_assemble_lowp(c->curve, c->lowp, o.lowp, o.lowp_band, o.lowp_outer == 1, c->alpha, c->beta,
+                                  nullptr, c->stream));
+    return RC_OK;
+  }
+  if (o.lowp) {
+    RC_TRY(launch_assemble_lowp(c->curve, c->lowp, o.lowp, o.lowp_band, o.lowp_outer == 1, c->alpha, c->beta,
+                                c->diag, c->stream));
+    c->lowp_levels = 1;
+    return RC_OK;
   }
   return launch_sobolev(c->curve, c->alpha, c->beta, c->dtype, c->x, c->tmp, c->diag, c->stream);
 }
