@@ -12,8 +12,13 @@ Definitions (paper Sec. 7.1 "Constraints and Potentials"):
 * Total length: ``Phi_L = L0 - sum_I l_I`` (1 row).
 * Edge length: ``Phi_I = l0_I - l_I`` (one row per edge) with Jacobian
   ``+T_I`` at i1 and ``-T_I`` at i2.
+* Loop length: the total-length constraint applied to every connected
+  component (closed loop) separately, ``Phi_q = L0_q - sum_{I in q} l_I``
+  (one row per component, components ordered by their smallest vertex), as a
+  packing of several curves keeps each curve's length.
 
-Rows are stacked in the order barycenter, total length, edge lengths.
+Rows are stacked in the order barycenter, total length, edge lengths, loop
+lengths.
 Vectors in R^{3|V|} are vertex-major: entry ``3 v + c`` is coordinate c of
 vertex v.
 """
@@ -24,11 +29,13 @@ import numpy as np
 
 from .tpe import edge_geometry
 
-__all__ = ["BARYCENTER", "TOTAL_LENGTH", "EDGE_LENGTH", "reference_values", "evaluate"]
+__all__ = ["BARYCENTER", "TOTAL_LENGTH", "EDGE_LENGTH", "LOOP_LENGTH", "reference_values", "components",
+           "loop_lengths", "evaluate"]
 
 BARYCENTER = 1
 TOTAL_LENGTH = 2
 EDGE_LENGTH = 4
+LOOP_LENGTH = 8
 
 
 def reference_values(gamma, edges):
@@ -40,8 +47,36 @@ def reference_values(gamma, edges):
     return (ell[:, None] * x).sum(0) / ell.sum(), float(ell.sum()), ell.copy()
 
 
-def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True):
-    """(Phi, C) for the constraint set ``mask`` (bitwise OR of the flags)."""
+def components(edges, n_vertices):
+    """Component index of every edge, components numbered by their smallest vertex."""
+    e = np.asarray(edges)
+    parent = list(range(n_vertices))
+
+    def find(v):
+        while parent[v] != v:
+            parent[v] = parent[parent[v]]
+            v = parent[v]
+        return v
+
+    for a, b in e:
+        ra, rb = find(int(a)), find(int(b))
+        if ra != rb:
+            parent[max(ra, rb)] = min(ra, rb)
+    roots = [find(int(a)) for a in e[:, 0]]
+    order = {r: k for k, r in enumerate(sorted(set(roots)))}
+    return np.array([order[r] for r in roots], dtype=np.int64)
+
+
+def loop_lengths(gamma, edges):
+    """Length of every component (the loop-length targets of gamma)."""
+    ell, _, _ = edge_geometry(gamma, edges)
+    comp = components(edges, len(gamma))
+    return np.bincount(comp, weights=ell)
+
+
+def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True, Lq=None):
+    """(Phi, C) for the constraint set ``mask`` (bitwise OR of the flags);
+    ``Lq`` are the loop-length targets."""
     g = np.asarray(gamma, dtype=np.float64)
     e = np.asarray(edges)
     nV, nE = len(g), len(e)
@@ -72,6 +107,16 @@ def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True):
                 Ce[I, 3 * e[I, 0]:3 * e[I, 0] + 3] = T[I]
                 Ce[I, 3 * e[I, 1]:3 * e[I, 1] + 3] = -T[I]
             jacs.append(Ce)
+    if mask & LOOP_LENGTH:
+        comp = components(e, nV)
+        nq = int(comp.max()) + 1
+        phis.append(np.asarray(Lq, dtype=np.float64) - np.bincount(comp, weights=ell, minlength=nq))
+        if jacobian:
+            Cq = np.zeros((nq, 3 * nV))
+            for I in range(nE):
+                Cq[comp[I], 3 * e[I, 0]:3 * e[I, 0] + 3] += T[I]
+                Cq[comp[I], 3 * e[I, 1]:3 * e[I, 1] + 3] -= T[I]
+            jacs.append(Cq)
     phi = np.concatenate(phis) if phis else np.zeros(0)
     if not jacobian:
         return phi, None

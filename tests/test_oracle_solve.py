@@ -93,3 +93,60 @@ def test_projection_transform_and_step(mask):
     ell, _, _ = tpe.edge_geometry(new, e)
     assert np.abs(phi_new).max() < 1e-9 * ell.sum()
     assert tpe.energy(new, e, 2.0, 4.5) == pytest.approx(info["E1"], rel=1e-14)
+
+
+def two_loops(seed=3):
+    """Two disjoint jittered circles of 18 and 23 edges (a small packing)."""
+    rng = np.random.default_rng(seed)
+    parts, edges, off = [], [], 0
+    for m, c in ((18, (0.0, 0.0, 0.0)), (23, (3.0, 0.5, -0.2))):
+        t = 2 * np.pi * np.arange(m) / m
+        p = np.stack([np.cos(t), np.sin(t), 0.3 * np.sin(2 * t)], 1) + np.asarray(c)
+        parts.append(p + 0.01 * rng.normal(size=p.shape))
+        edges.append(gen.loop_edges(m, off))
+        off += m
+    return np.concatenate(parts), np.concatenate(edges)
+
+
+def test_loop_length_jacobian_and_identities():
+    g, e = two_loops()
+    x0, L0, l0 = cons.reference_values(g, e)
+    Lq = cons.loop_lengths(g, e)
+    assert len(Lq) == 2 and abs(Lq.sum() - L0) < 1e-12 * L0
+    mask = cons.BARYCENTER | cons.LOOP_LENGTH
+    phi, C = cons.evaluate(g, e, mask, x0, Lq=Lq)
+    assert C.shape == (5, 3 * len(g)) and np.abs(phi).max() < 1e-12
+    # central differences of Phi
+    h = 1e-6
+    for v, c in [(0, 0), (17, 2), (18, 1), (40, 0)]:
+        gp, gm = g.copy(), g.copy()
+        gp[v, c] += h
+        gm[v, c] -= h
+        fd = (cons.evaluate(gp, e, mask, x0, Lq=Lq, jacobian=False)[0]
+              - cons.evaluate(gm, e, mask, x0, Lq=Lq, jacobian=False)[0]) / (2 * h)
+        assert np.allclose(C[:, 3 * v + c], fd, rtol=1e-7, atol=1e-8)
+    # a loop row only touches its own loop's vertices
+    assert np.abs(C[3, 3 * 18:]).max() == 0 and np.abs(C[4, :3 * 18]).max() == 0
+    # the loop rows sum to the total-length row
+    _, Ct = cons.evaluate(g, e, cons.TOTAL_LENGTH, L0=L0)
+    assert np.abs(C[3] + C[4] - Ct[0]).max() < 1e-14
+    # on a single loop the loop-length row is the total-length row
+    g1, e1 = gen.trefoil(30, seed=4)
+    p1, C1 = cons.evaluate(g1, e1, cons.LOOP_LENGTH, Lq=cons.loop_lengths(g1, e1) + 0.1)
+    p2, C2 = cons.evaluate(g1, e1, cons.TOTAL_LENGTH, L0=cons.reference_values(g1, e1)[1] + 0.1)
+    assert np.allclose(p1, p2, atol=1e-14) and np.abs(C1 - C2).max() == 0
+
+
+def test_loop_length_saddle_kkt():
+    g, e = two_loops()
+    x0, _, _ = cons.reference_values(g, e)
+    Lq = cons.loop_lengths(g, e)
+    _, dE = tpe.differential(g, e, 3.0, 6.0)
+    A = sum(sobolev.assemble(g, e, 3.0, 6.0))
+    _, C = cons.evaluate(g, e, cons.BARYCENTER | cons.LOOP_LENGTH, x0, Lq=Lq)
+    gt, lam = solve.projected_gradient(A, C, dE)
+    gs, _ = solve.projected_gradient_schur(A, C, dE)
+    assert np.abs(gt - gs).max() < 1e-10 * np.abs(gt).max()
+    assert np.abs(C @ gt.ravel()).max() < 1e-10 * np.abs(gt).max()
+    kkt = np.kron(A, np.eye(3)) @ gt.ravel() + C.T @ lam - dE.ravel()
+    assert np.abs(kkt).max() < 1e-9 * np.abs(dE).max()
