@@ -91,6 +91,22 @@ typedef struct {
                             residual has dropped by this factor (0 = only at tol) */
 } rc_solve_opts;
 
+/* Options of the batch step (rc_batch_step). */
+typedef struct {
+  double tol;            /* relative residual of each instance's projected PCG (FP32 operator) */
+  int32_t max_iter;      /* PCG iterations of the gradient solve (a fixed count in a captured step) */
+  int32_t ls_rounds;     /* step lengths tried: tau0, tau0/2, ... */
+  int32_t proj_iters;    /* constraint projection iterations per trial step */
+  int32_t proj_max_iter; /* PCG iterations of each projection solve */
+  double proj_tol;       /* relative PCG tolerance of the projection solves */
+  double accept_tol;     /* a trial is accepted only if |Phi| <= accept_tol times the constraint scale */
+  double c_armijo;       /* sufficient-decrease constant */
+  double tau0;           /* first step length (after normalising each instance's gradient) */
+  int32_t graph;         /* 1 = capture the whole step in a hipGraph on first use and replay it */
+  int32_t check_every;   /* without graph: stop the PCG once every instance has converged, checked
+                            every check_every iterations (0 = run max_iter) */
+} rc_batch_opts;
+
 typedef struct {
   double c_armijo;       /* sufficient-decrease constant */
   double shrink;         /* step shrink factor */
@@ -252,6 +268,80 @@ rc_status rc_lowp_assemble(rc_ctx* ctx, const double* gamma, int32_t fmt, int32_
  * X, Y: device double [nV][3]; Y is overwritten.  RC_ERR_ARG if that block
  * has not been assembled. */
 rc_status rc_lowp_apply(rc_ctx* ctx, const double* X, double* Y, int32_t f32);
+
+/* Sphere-obstacle penalty (Sec. 7.1, surface potential with M a sphere of
+ * centre c and radius R): weight * sum_I l_I Psi(|x_I - c|), with Psi the
+ * closed-form integral of |x_M - y|^-(beta - alpha) over the sphere and one
+ * midpoint sample per edge.  It is added to every energy and differential of
+ * the context (single curves and batches).  center_h: host double[3];
+ * radius > 0; weight > 0, or weight = 0 to remove it (else RC_ERR_ARG).  An
+ * edge midpoint on or inside the sphere gives an infinite energy. */
+rc_status rc_set_obstacle(rc_ctx* ctx, const double* center_h, double radius, double weight);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent curve networks ("instances", e.g. packings of
+ * closed loops) in one context.  Pair sums (energy, differential, operator)
+ * run over pairs of edges of the same instance only, as one persistent launch
+ * over work items (target tile, source range) ordered longest first.
+ * ---------------------------------------------------------------------- */
+
+/* Creates a batch context.  inst_vertex_off_h: host int32[n_inst + 1],
+ * increasing, from 0 to n_vertices: instance i owns vertices
+ * [off[i], off[i+1]).  edges_h: host int32[n_edges][2], grouped by instance in
+ * instance order, every edge inside one instance.  Other arguments and
+ * errors as rc_create.  rc_energy / rc_differential / rc_sobolev_apply then
+ * give the sums over all instances (the block-diagonal operator); the
+ * single-network solver calls return RC_ERR_UNSUPPORTED on a batch. */
+rc_status rc_create_batch(int32_t n_inst, const int32_t* inst_vertex_off_h, int32_t n_vertices, int32_t n_edges,
+                          const int32_t* edges_h, double alpha, double beta, rc_dtype dtype, rc_stream stream,
+                          rc_ctx** out);
+
+/* Number of instances (0 for a single-network context). */
+int32_t rc_batch_size(const rc_ctx* ctx);
+
+/* Per-instance energies (device double[n_inst]) and, when dE != NULL, the
+ * differential (device double[nV][3]); the obstacle is included when set. */
+rc_status rc_batch_energies(rc_ctx* ctx, const double* gamma, double* energies, double* dE);
+
+/* Work-item shape of the batch pair kernels: source ranges of src_chunk
+ * edges (256 .. 2^20) and blocks_per_cu persistent workgroups per compute
+ * unit (1 .. 32).  Synchronises the stream. */
+rc_status rc_batch_tiling(rc_ctx* ctx, int32_t src_chunk, int32_t blocks_per_cu);
+
+/* Defaults of rc_batch_opts. */
+void rc_default_batch_opts(rc_batch_opts* opts);
+
+/* Constraint targets of every instance from gamma_ref (device double
+ * [nV][3]): the length-weighted barycenter of the instance (Sec. 7.1,
+ * barycenter) and the length of each of its loops (Sec. 7.1, total length,
+ * one row per loop).  Needed before rc_batch_gradient / rc_batch_step. */
+rc_status rc_batch_set_constraints(rc_ctx* ctx, const double* gamma_ref);
+
+/* Projected Sobolev gradient of every instance (eq.
+ * GradientSaddlePointProblem with that instance's constraints): PCG with the
+ * FP32 operator, the loop-block preconditioner and per-instance scalars, to
+ * opts->tol or opts->max_iter.  dE, g: device double[nV][3]. */
+rc_status rc_batch_gradient(rc_ctx* ctx, const double* gamma, const double* dE, double* g,
+                            const rc_batch_opts* opts);
+
+/* One projected Sobolev step of every instance (Sec. 4.3-4.4): energy and
+ * differential, gradient as rc_batch_gradient, then per instance: normalise,
+ * try tau0, tau0/2, ... (opts->ls_rounds lengths), project each trial back
+ * onto the constraints (opts->proj_iters increments of eq.
+ * ConstraintSaddlePointProblem via eq. SaddleSolutionTransformation, with
+ * the operator and Jacobian frozen at gamma), accept the first length that
+ * satisfies Armijo and |Phi| <= opts->accept_tol.  gamma (device, in place)
+ * changes only for instances that accepted.  With opts->graph = 1 the step is
+ * captured once as a hipGraph (fixed trip counts, no host synchronisation)
+ * and replayed; a change of gamma's address or of the options recaptures.
+ * stats_h: host double[n_inst][8] or NULL: (E0, E1, tau, PCG iterations,
+ * PCG residual, status 0 accepted / 1 no step / 2 singular constraints, |g|,
+ * halvings); filling it synchronises. */
+rc_status rc_batch_step(rc_ctx* ctx, double* gamma, const rc_batch_opts* opts, double* stats_h);
+
+/* Iterations and relative residual of every instance in the last batch PCG
+ * solve (host double[n_inst] each); synchronises. */
+rc_status rc_batch_pcg_state(rc_ctx* ctx, double* iters_h, double* res_h);
 
 /* Kernel timing with HIP events on the context's stream.  rc_profile_enable
  * clears earlier records and, when enable != 0, brackets every launch of the

@@ -15,8 +15,10 @@ from ._lib import (  # noqa: F401
     RC_SOLVE_DENSE,
     RC_SOLVE_PCG_JACOBI,
     RC_SOLVE_PCG_MG,
+    Batch,
     Context,
     RcError,
+    default_batch_opts,
     default_ls_opts,
     default_solve_opts,
     load,

@@ -31,7 +31,9 @@ EXPORTED = [
     "rc_differential", "rc_sobolev_apply", "rc_sobolev_apply_prec", "rc_sobolev_diag", "rc_assemble_dense",
     "rc_set_constraints", "rc_constraint_values", "rc_constraint_count", "rc_project", "rc_sobolev_gradient",
     "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_bh_last_work", "rc_midpoint_differential",
-    "rc_profile_enable", "rc_profile_read", "rc_lowp_assemble", "rc_lowp_apply",
+    "rc_profile_enable", "rc_profile_read", "rc_lowp_assemble", "rc_lowp_apply", "rc_set_obstacle",
+    "rc_create_batch", "rc_batch_size", "rc_batch_energies", "rc_batch_tiling", "rc_default_batch_opts",
+    "rc_batch_set_constraints", "rc_batch_gradient", "rc_batch_step", "rc_batch_pcg_state",
 ]
 
 
@@ -46,6 +48,12 @@ class SolveOpts(C.Structure):
                 ("replace_every", C.c_int32), ("mg_min_vertices", C.c_int32), ("cheb_degree", C.c_int32),
                 ("op_f64", C.c_int32), ("lowp", C.c_int32), ("lowp_band", C.c_int32),
                 ("lowp_min_vertices", C.c_int32), ("lowp_outer", C.c_int32), ("inner_tol", C.c_double)]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("ls_rounds", C.c_int32), ("proj_iters", C.c_int32),
+                ("proj_max_iter", C.c_int32), ("proj_tol", C.c_double), ("accept_tol", C.c_double),
+                ("c_armijo", C.c_double), ("tau0", C.c_double), ("graph", C.c_int32), ("check_every", C.c_int32)]
 
 
 class LsOpts(C.Structure):
@@ -103,6 +111,16 @@ def load():
         "rc_profile_enable": (I32, [P, I32]),
         "rc_profile_read": (I32, [P, I32, C.POINTER(D), C.POINTER(I32)]),
         "rc_lowp_assemble": (I32, [P, P, I32, I32, I32]),
+        "rc_set_obstacle": (I32, [P, P, D, D]),
+        "rc_create_batch": (I32, [I32, P, I32, I32, P, D, D, I32, P, P]),
+        "rc_batch_size": (I32, [P]),
+        "rc_batch_energies": (I32, [P, P, P, P]),
+        "rc_batch_tiling": (I32, [P, I32, I32]),
+        "rc_default_batch_opts": (None, [P]),
+        "rc_batch_set_constraints": (I32, [P, P]),
+        "rc_batch_gradient": (I32, [P, P, P, P, P]),
+        "rc_batch_step": (I32, [P, P, P, P]),
+        "rc_batch_pcg_state": (I32, [P, P, P]),
         "rc_lowp_apply": (I32, [P, P, P, I32]),
     }
     for name, (res, args) in sig.items():
@@ -145,6 +163,14 @@ def _stream():
 def default_solve_opts(**kw):
     o = SolveOpts()
     load().rc_default_solve_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def default_batch_opts(**kw):
+    o = BatchOpts()
+    load().rc_default_batch_opts(C.byref(o))
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -274,7 +300,62 @@ class Context:
     def rc_lowp_apply(self, X, Y, f32=False):
         _check(load().rc_lowp_apply(self.h, self._v(X, "X"), self._v(Y, "Y"), 1 if f32 else 0))
 
+    def rc_set_obstacle(self, center, radius, weight=1.0):
+        self._c = (C.c_double * 3)(*[float(v) for v in center])
+        _check(load().rc_set_obstacle(self.h, C.cast(self._c, C.c_void_p), float(radius), float(weight)))
+
     def rc_bh_last_work(self):
         f, n, nodes, depth = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32()
         _check(load().rc_bh_last_work(self.h, C.byref(f), C.byref(n), C.byref(nodes), C.byref(depth)))
         return {"far": f.value, "near": n.value, "nodes": nodes.value, "depth": depth.value}
+
+
+class Batch(Context):
+    """A batch context: independent instances (vertex ranges) in one library context."""
+
+    def __init__(self, inst_vertex_off, edges, alpha, beta, dtype=RC_F32):
+        lib = load()
+        off = np.ascontiguousarray(np.asarray(inst_vertex_off, dtype=np.int32))
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32))
+        if off.ndim != 1 or len(off) < 2:
+            raise ValueError("inst_vertex_off must be [n_inst + 1]")
+        if e.ndim != 2 or e.shape[1] != 2:
+            raise ValueError("edges must be [n_edges, 2]")
+        self.nV, self.nE, self.n_inst = int(off[-1]), int(e.shape[0]), len(off) - 1
+        self.alpha, self.beta, self.dtype = float(alpha), float(beta), int(dtype)
+        h = C.c_void_p()
+        _check(lib.rc_create_batch(self.n_inst, off.ctypes.data_as(C.c_void_p), self.nV, self.nE,
+                                   e.ctypes.data_as(C.c_void_p), self.alpha, self.beta, self.dtype, _stream(),
+                                   C.byref(h)))
+        self.h = h
+        import torch
+
+        self._f64 = torch.float64
+
+    def rc_batch_energies(self, gamma, energies, dE=None):
+        _check(load().rc_batch_energies(self.h, self._v(gamma, "gamma"),
+                                        _ptr(energies, (self.n_inst,), self._f64, "energies"),
+                                        None if dE is None else self._v(dE, "dE")))
+
+    def rc_batch_tiling(self, src_chunk, blocks_per_cu):
+        _check(load().rc_batch_tiling(self.h, int(src_chunk), int(blocks_per_cu)))
+
+    def rc_batch_set_constraints(self, gamma_ref):
+        _check(load().rc_batch_set_constraints(self.h, self._v(gamma_ref, "gamma_ref")))
+
+    def rc_batch_gradient(self, gamma, dE, g, opts=None):
+        o = opts if opts is not None else default_batch_opts()
+        _check(load().rc_batch_gradient(self.h, self._v(gamma, "gamma"), self._v(dE, "dE"), self._v(g, "g"),
+                                        C.byref(o)))
+
+    def rc_batch_step(self, gamma, opts=None, stats=True):
+        o = opts if opts is not None else default_batch_opts()
+        out = np.zeros((self.n_inst, 8)) if stats else None
+        _check(load().rc_batch_step(self.h, self._v(gamma, "gamma"), C.byref(o),
+                                    None if out is None else out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def rc_batch_pcg_state(self):
+        it, res = np.zeros(self.n_inst), np.zeros(self.n_inst)
+        _check(load().rc_batch_pcg_state(self.h, it.ctypes.data_as(C.c_void_p), res.ctypes.data_as(C.c_void_p)))
+        return it, res

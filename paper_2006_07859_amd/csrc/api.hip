@@ -54,6 +54,15 @@ rc_status check_ptrs(std::initializer_list<const void*> ps) {
   return RC_OK;
 }
 
+// Entry points whose sums or solves assume one network reject batch contexts.
+rc_status no_batch(const rc_ctx* c, const char* name) {
+  if (c->curve.n_inst > 0) {
+    set_error(std::string(name) + ": not available on a batch context (use the rc_batch_* calls)");
+    return RC_ERR_UNSUPPORTED;
+  }
+  return RC_OK;
+}
+
 rc_solve_opts resolve(const rc_solve_opts* o) {
   rc_solve_opts d;
   rc_default_solve_opts(&d);
@@ -107,8 +116,9 @@ void rc_default_ls_opts(rc_ls_opts* o) {
 
 const char* rc_last_error(void) { return rc::last_error(); }
 
-rc_status rc_create(int32_t nV, int32_t nE, const int32_t* edges_h, double alpha, double beta, rc_dtype dtype,
-                    rc_stream stream, rc_ctx** out) {
+static rc_status create_ctx(int32_t nV, int32_t nE, const int32_t* edges_h, double alpha, double beta,
+                            rc_dtype dtype, rc_stream stream, int32_t n_inst, const int32_t* voff_h,
+                            rc_ctx** out) {
   set_error("");
   if (!out || !edges_h || nV <= 0 || nE <= 0) {
     set_error("rc_create: null pointer or empty curve");
@@ -141,6 +151,10 @@ rc_status rc_create(int32_t nV, int32_t nE, const int32_t* edges_h, double alpha
   c->dtype = dtype;
   c->stream = (hipStream_t)stream;
   RC_TRY(c->curve.init(nV, nE, edges_h));
+  if (n_inst > 0) {
+    RC_TRY(c->curve.set_instances(n_inst, voff_h));
+    RC_TRY(batch_alloc(c.get()));
+  }
   const size_t n3 = 3 * (size_t)nV;
   double** vecs[] = {&c->x,    &c->r,    &c->z,   &c->p,  &c->q,   &c->tmp, &c->tmp2,
                      &c->trial, &c->zmin, &c->inc, &c->dx, &c->dEs, &c->gs};
@@ -155,12 +169,29 @@ rc_status rc_create(int32_t nV, int32_t nE, const int32_t* edges_h, double alpha
   return RC_OK;
 }
 
+rc_status rc_create(int32_t nV, int32_t nE, const int32_t* edges_h, double alpha, double beta, rc_dtype dtype,
+                    rc_stream stream, rc_ctx** out) {
+  return create_ctx(nV, nE, edges_h, alpha, beta, dtype, stream, 0, nullptr, out);
+}
+
+rc_status rc_create_batch(int32_t n_inst, const int32_t* inst_vertex_off_h, int32_t n_vertices, int32_t n_edges,
+                          const int32_t* edges_h, double alpha, double beta, rc_dtype dtype, rc_stream stream,
+                          rc_ctx** out) {
+  set_error("");
+  if (n_inst < 1 || !inst_vertex_off_h) {
+    set_error("rc_create_batch: need at least one instance and its vertex offsets");
+    return RC_ERR_ARG;
+  }
+  return create_ctx(n_vertices, n_edges, edges_h, alpha, beta, dtype, stream, n_inst, inst_vertex_off_h, out);
+}
+
 rc_status rc_destroy(rc_ctx* c) {
   if (!c) return RC_OK;
   hipStreamSynchronize(c->stream);
   c->timer.clear();
   c->bvh.release();
   c->lowp.release();
+  batch_free(c);
   mg_free(c);
   dense_free(c->dense);
   cons_free(c->cons);
@@ -213,6 +244,7 @@ rc_status rc_sobolev_diag(rc_ctx* c, const double* gamma, double* diag) {
 
 rc_status rc_assemble_dense(rc_ctx* c, const double* gamma, double* A) {
   RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_assemble_dense"));
   RC_TRY(check_ptrs({gamma, A}));
   RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));
   return launch_assemble_dense(c->curve, c->alpha, c->beta, A, c->stream);
@@ -221,6 +253,7 @@ rc_status rc_assemble_dense(rc_ctx* c, const double* gamma, double* A) {
 rc_status rc_set_constraints(rc_ctx* c, uint32_t mask, const double* gamma_ref, const double* x0_h,
                              double total_len0, const double* edge_len0) {
   RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_set_constraints"));
   if (mask & ~7u) {
     set_error("unknown constraint flag");
     return RC_ERR_ARG;
@@ -249,6 +282,7 @@ int32_t rc_constraint_count(const rc_ctx* c) { return c ? c->cons.k : 0; }
 
 rc_status rc_constraint_values(rc_ctx* c, const double* gamma, double* phi) {
   RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_constraint_values"));
   RC_TRY(check_ptrs({gamma, phi}));
   if (c->cons.k == 0) return RC_OK;
   cons_values(c, gamma, phi);
@@ -258,6 +292,7 @@ rc_status rc_constraint_values(rc_ctx* c, const double* gamma, double* phi) {
 
 rc_status rc_project(rc_ctx* c, const double* gamma, const double* X, double* Y) {
   RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_project"));
   RC_TRY(check_ptrs({gamma, X, Y}));
   RC_TRY(cons_prepare(c, c->curve, c->cons, gamma));
   cons_project(c, c->curve, c->cons, X, Y);
@@ -268,6 +303,7 @@ rc_status rc_project(rc_ctx* c, const double* gamma, const double* X, double* Y)
 rc_status rc_sobolev_gradient(rc_ctx* c, const double* gamma, const double* dE, double* g,
                               const rc_solve_opts* opts, rc_stats* stats) {
   RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_sobolev_gradient"));
   RC_TRY(check_ptrs({gamma, dE, g}));
   rc_solve_opts o = resolve(opts);
   RC_TRY(prepare_solver(c, gamma, o));
@@ -286,6 +322,7 @@ rc_status rc_sobolev_gradient(rc_ctx* c, const double* gamma, const double* dE, 
 rc_status rc_line_search_step(rc_ctx* c, double* gamma, double energy0, const double* dE, const double* g,
                               const rc_ls_opts* ls, const rc_solve_opts* so, double* tau_h, rc_stats* stats) {
   RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_line_search_step"));
   RC_TRY(check_ptrs({gamma, dE, g}));
   rc_solve_opts o = resolve(so);
   rc_ls_opts l = resolve_ls(ls);
@@ -306,6 +343,7 @@ rc_status rc_line_search_step(rc_ctx* c, double* gamma, double energy0, const do
 
 rc_status rc_step(rc_ctx* c, double* gamma, const rc_solve_opts* so, const rc_ls_opts* ls, rc_stats* stats) {
   RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_step"));
   RC_TRY(check_ptrs({gamma}));
   rc_solve_opts o = resolve(so);
   rc_ls_opts l = resolve_ls(ls);
@@ -371,6 +409,7 @@ rc_status rc_step(rc_ctx* c, double* gamma, const rc_solve_opts* so, const rc_ls
 
 extern "C" rc_status rc_midpoint_differential(rc_ctx* c, const double* gamma, double* energy, double* dE) {
   RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_midpoint_differential"));
   RC_TRY(check_ptrs({gamma, dE}));
   RC_TRY(launch_geometry(c->curve, gamma, c->dtype, c->stream));
   return launch_midpoint(c->curve, c->alpha, c->beta, c->dtype, energy, dE, c->stream);
@@ -410,6 +449,7 @@ extern "C" rc_status rc_profile_read(rc_ctx* c, int32_t which, double* total_ms,
 extern "C" rc_status rc_bh_differential(rc_ctx* c, const double* gamma, double theta, int32_t leaf_size,
                                         double* energy, double* dE) {
   RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_bh_differential"));
   RC_TRY(check_ptrs({gamma, dE}));
   if (!(theta > 0.0) || !(theta < 0.5)) {
     set_error("rc_bh_differential: theta must lie in (0, 0.5) so that a target's own cluster is never admissible");
@@ -443,6 +483,7 @@ extern "C" rc_status rc_bh_last_work(rc_ctx* c, int64_t* far_pairs, int64_t* nea
 
 extern "C" rc_status rc_lowp_assemble(rc_ctx* c, const double* gamma, int32_t fmt, int32_t band, int32_t with_f32) {
   RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_lowp_assemble"));
   RC_TRY(check_ptrs({gamma}));
   if (fmt != 1 && fmt != 2) {
     set_error("rc_lowp_assemble: fmt must be 1 (BF16) or 2 (FP16)");
@@ -461,4 +502,129 @@ extern "C" rc_status rc_lowp_apply(rc_ctx* c, const double* X, double* Y, int32_
   RC_TRY(check_ptrs({X, Y}));
   if (f32) return launch_lowp_apply32(c->lowp, X, Y, c->stream, &c->timer);
   return launch_lowp_apply(c->lowp, X, Y, c->stream, &c->timer);
+}
+
+// ---------------------------------------------------------------------------
+// obstacle and batch entry points
+// ---------------------------------------------------------------------------
+extern "C" rc_status rc_set_obstacle(rc_ctx* c, const double* center_h, double radius, double weight) {
+  RC_TRY(check_ctx(c));
+  Obstacle& o = c->curve.obstacle;
+  if (weight == 0.0) {
+    o.on = false;
+    return RC_OK;
+  }
+  RC_TRY(check_ptrs({center_h}));
+  if (!(radius > 0.0) || !std::isfinite(weight) || !(weight > 0.0)) {
+    set_error("rc_set_obstacle: need radius > 0 and weight > 0 (weight 0 removes the obstacle)");
+    return RC_ERR_ARG;
+  }
+  o.on = true;
+  o.c[0] = center_h[0];
+  o.c[1] = center_h[1];
+  o.c[2] = center_h[2];
+  o.R = radius;
+  o.p = c->beta - c->alpha;
+  o.w = weight;
+  return RC_OK;
+}
+
+extern "C" int32_t rc_batch_size(const rc_ctx* c) { return c ? c->curve.n_inst : 0; }
+
+extern "C" rc_status rc_batch_energies(rc_ctx* c, const double* gamma, double* energies, double* dE) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(check_ptrs({gamma, energies}));
+  if (c->curve.n_inst == 0) {
+    set_error("rc_batch_energies: not a batch context");
+    return RC_ERR_ARG;
+  }
+  RC_TRY(launch_geometry(c->curve, gamma, c->dtype, c->stream));
+  RC_TRY(launch_tpe(c->curve, c->alpha, c->beta, c->dtype, dE != nullptr, nullptr, dE, c->stream));
+  return batch_edge_sums(c, 0, energies);
+}
+
+extern "C" rc_status rc_batch_tiling(rc_ctx* c, int32_t src_chunk, int32_t blocks_per_cu) {
+  RC_TRY(check_ctx(c));
+  if (c->curve.n_inst == 0) {
+    set_error("rc_batch_tiling: not a batch context");
+    return RC_ERR_ARG;
+  }
+  RC_HIP(hipStreamSynchronize(c->stream));
+  return c->curve.build_items(src_chunk, blocks_per_cu);
+}
+
+extern "C" void rc_default_batch_opts(rc_batch_opts* o) {
+  if (!o) return;
+  o->tol = 1e-4;
+  o->max_iter = 120;
+  o->ls_rounds = 4;
+  o->proj_iters = 2;
+  o->proj_max_iter = 20;
+  o->proj_tol = 1e-3;
+  o->accept_tol = 1e-6;
+  o->c_armijo = 0.01;
+  o->tau0 = 1.0;
+  o->graph = 0;
+  o->check_every = 5;
+}
+
+static rc_status batch_ctx(rc_ctx* c, const char* name) {
+  RC_TRY(check_ctx(c));
+  if (c->curve.n_inst == 0) {
+    set_error(std::string(name) + ": not a batch context");
+    return RC_ERR_ARG;
+  }
+  return RC_OK;
+}
+
+static rc_status batch_opts(const rc_batch_opts* in, rc_batch_opts* o) {
+  rc_default_batch_opts(o);
+  if (in) *o = *in;
+  if (!(o->tol > 0) || o->max_iter < 1 || o->ls_rounds < 1 || o->proj_iters < 0 || o->proj_max_iter < 1 ||
+      !(o->proj_tol > 0) || !(o->accept_tol > 0) || !(o->c_armijo > 0) || !(o->tau0 > 0) || o->check_every < 0) {
+    set_error("batch options out of range");
+    return RC_ERR_ARG;
+  }
+  if (o->max_iter > 10000 || o->ls_rounds > 60 || o->proj_iters > 20 || o->proj_max_iter > 10000) {
+    set_error("batch options: trip counts too large");
+    return RC_ERR_ARG;
+  }
+  return RC_OK;
+}
+
+extern "C" rc_status rc_batch_set_constraints(rc_ctx* c, const double* gamma_ref) {
+  RC_TRY(batch_ctx(c, "rc_batch_set_constraints"));
+  RC_TRY(check_ptrs({gamma_ref}));
+  return batch_set_constraints(c, gamma_ref);
+}
+
+extern "C" rc_status rc_batch_gradient(rc_ctx* c, const double* gamma, const double* dE, double* g,
+                                       const rc_batch_opts* opts) {
+  RC_TRY(batch_ctx(c, "rc_batch_gradient"));
+  RC_TRY(check_ptrs({gamma, dE, g}));
+  rc_batch_opts o;
+  RC_TRY(batch_opts(opts, &o));
+  return batch_gradient(c, gamma, dE, g, o);
+}
+
+extern "C" rc_status rc_batch_step(rc_ctx* c, double* gamma, const rc_batch_opts* opts, double* stats_h) {
+  RC_TRY(batch_ctx(c, "rc_batch_step"));
+  RC_TRY(check_ptrs({gamma}));
+  rc_batch_opts o;
+  RC_TRY(batch_opts(opts, &o));
+  return batch_step(c, gamma, o, stats_h);
+}
+
+extern "C" rc_status rc_batch_pcg_state(rc_ctx* c, double* iters_h, double* res_h) {
+  RC_TRY(batch_ctx(c, "rc_batch_pcg_state"));
+  RC_TRY(check_ptrs({iters_h, res_h}));
+  const int n = c->curve.n_inst;
+  std::vector<double> sc((size_t)kBatchScal * n);
+  RC_HIP(hipMemcpyAsync(sc.data(), c->batch.sc, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, c->stream));
+  RC_HIP(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < n; ++i) {
+    iters_h[i] = sc[(size_t)i * kBatchScal + 8];
+    res_h[i] = sc[(size_t)i * kBatchScal + 6];
+  }
+  return RC_OK;
 }

@@ -1,0 +1,988 @@
+// Batch of independent packing instances in one context: every instance is a
+// set of closed loops (a curve network whose components are chains), with a
+// barycenter constraint per instance and a length constraint per loop
+// (Sec. 7.1, total length applied to each curve), the sphere-obstacle
+// penalty, and its own projected Sobolev gradient (eq.
+// GradientSaddlePointProblem) and backtracking step (Sec. 4.3-4.4).
+//
+// The pair sums run as one persistent launch over all instances (k_pairs.hip,
+// work items restricted to one instance).  Everything else is batched by
+// instance or by loop: segmented reductions with one workgroup per instance
+// or loop, per-instance PCG scalars kept on the device, a per-instance step
+// length.  The step has no host synchronisation, so it can be captured in a
+// hipGraph with fixed trip counts; instances that have converged (or
+// accepted their step) are frozen by device-side flags.
+//
+// Preconditioner: block Jacobi by loop.  Each loop's block of A (the loop's
+// own rows and columns, with the full diagonal, which carries the loop's
+// coupling to the other loops) is assembled in FP64 and inverted exactly by
+// Gauss-Jordan; it is applied as P M^-1 P.  The other loops act only through
+// the smooth far field, which PCG resolves in few iterations.
+//
+// Constraint algebra: C C^T of an instance has an arrow structure (a 3x3
+// barycenter block, a diagonal block of the loops, and their coupling), so
+// (C C^T)^-1 is applied through the 3x3 Schur complement of the diagonal
+// block, with O(loops) work per instance.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "k_linalg.h"
+#include "pair_math.h"
+#include "solver.h"
+
+namespace rc {
+
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+template <typename T>
+static rc_status balloc(T** p, size_t n) {
+  *p = nullptr;
+  hipError_t e = hipMalloc((void**)p, sizeof(T) * std::max<size_t>(n, 1));
+  if (e != hipSuccess) {
+    set_error(std::string("batch allocation failed: ") + hipGetErrorString(e));
+    return RC_ERR_NOMEM;
+  }
+  return RC_OK;
+}
+
+// scalar slots
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_RES, S_ACT, S_ITS };
+enum { L_E0 = 0, L_E1, L_SLOPE, L_TAU, L_DONE, L_GN, L_PHI, L_TAUACC, L_BT, L_SCALE, L_RES, L_ITS };
+
+// ---------------------------------------------------------------------------
+// segmented reductions (one workgroup of 256 per segment, fixed order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* sm) {
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sm[0];
+  __syncthreads();
+  return r;
+}
+
+// Per instance: out[i][slot] = sum over its vertices of x . y (3 components).
+__global__ __launch_bounds__(256) void k_b_dot(const double* __restrict__ x, const double* __restrict__ y,
+                                               const int* __restrict__ voff, double* __restrict__ out, int stride,
+                                               int slot) {
+  __shared__ double sm[256];
+  const int i = blockIdx.x;
+  const int a = 3 * voff[i], b = 3 * voff[i + 1];
+  double s = 0.0;
+  for (int k = a + threadIdx.x; k < b; k += 256) s += x[k] * y[k];
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) out[(size_t)i * stride + slot] = s;
+}
+
+// Per instance: edge_out slot sums (energies).
+__global__ __launch_bounds__(256) void k_b_edge_sum(const double* __restrict__ edge_out, int slot,
+                                                    const int* __restrict__ eoff, double* __restrict__ out) {
+  __shared__ double sm[256];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int I = eoff[i] + threadIdx.x; I < eoff[i + 1]; I += 256) s += edge_out[8 * (size_t)I + slot];
+  s = block_sum(s, sm);
+  if (threadIdx.x == 0) out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// constraints: barycenter per instance, length per loop
+// ---------------------------------------------------------------------------
+// Per vertex v (with s = -1 at an edge's first endpoint, +1 at its second):
+//   J_v = sum_{I at v} (l_I / 2) Id_3 + s (x_I - x0) T_I^T   (barycenter rows)
+//   L_v = sum_{I at v} -s T_I                             (its loop's length row)
+// for Phi_b = sum_I l_I (x_I - x0) and Phi_q = L0_q - sum_{I in q} l_I.
+__global__ void k_b_rows(const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB,
+                         const V4<double>* __restrict__ GT, const int* __restrict__ inc_off,
+                         const int* __restrict__ inc, const int* __restrict__ inst_of_vertex,
+                         const double* __restrict__ x0, int nV, double* __restrict__ Jv, double* __restrict__ Lv) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nV) return;
+  const int i = inst_of_vertex[v];
+  const double ox = x0[3 * i], oy = x0[3 * i + 1], oz = x0[3 * i + 2];
+  double J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, L[3] = {0, 0, 0};
+  for (int k = inc_off[v]; k < inc_off[v + 1]; ++k) {
+    const int I = inc[k] >> 1;
+    const double s = (inc[k] & 1) ? 1.0 : -1.0;
+    const V4<double> a = GA[I], b = GB[I], t = GT[I];
+    const double d[3] = {0.5 * (a.x + b.x) - ox, 0.5 * (a.y + b.y) - oy, 0.5 * (a.z + b.z) - oz};
+    const double T[3] = {t.x, t.y, t.z};
+    for (int r = 0; r < 3; ++r) {
+      J[4 * r] += 0.5 * a.w;
+      for (int q = 0; q < 3; ++q) J[3 * r + q] += s * d[r] * T[q];
+      L[r] -= s * T[r];
+    }
+  }
+  for (int k = 0; k < 9; ++k) Jv[9 * (size_t)v + k] = J[k];
+  for (int k = 0; k < 3; ++k) Lv[3 * (size_t)v + k] = L[k];
+}
+
+// Per loop: qsum = (J J^T (9, row-major), J L (3), L . L) summed over its vertices.
+__global__ __launch_bounds__(256) void k_b_qsum(const double* __restrict__ Jv, const double* __restrict__ Lv,
+                                                const int* __restrict__ chain_vert, const int* __restrict__ chain_voff,
+                                                double* __restrict__ qsum) {
+  __shared__ double sm[256];
+  const int q = blockIdx.x;
+  double acc[13];
+  for (int k = 0; k < 13; ++k) acc[k] = 0.0;
+  for (int k = chain_voff[q] + threadIdx.x; k < chain_voff[q + 1]; k += 256) {
+    const int v = chain_vert[k];
+    const double* J = Jv + 9 * (size_t)v;
+    const double* L = Lv + 3 * (size_t)v;
+    for (int a = 0; a < 3; ++a) {
+      for (int b = 0; b < 3; ++b) acc[3 * a + b] += J[3 * a] * J[3 * b] + J[3 * a + 1] * J[3 * b + 1] + J[3 * a + 2] * J[3 * b + 2];
+      acc[9 + a] += J[3 * a] * L[0] + J[3 * a + 1] * L[1] + J[3 * a + 2] * L[2];
+    }
+    acc[12] += L[0] * L[0] + L[1] * L[1] + L[2] * L[2];
+  }
+  for (int k = 0; k < 13; ++k) {
+    const double s = block_sum(acc[k], sm);
+    if (threadIdx.x == 0) qsum[16 * (size_t)q + k] = s;
+  }
+}
+
+__device__ bool inv3(const double* A, double* X) {
+  const double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
+  const double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+  if (!(fabs(det) > 0.0) || !isfinite(det)) return false;
+  const double id = 1.0 / det;
+  X[0] = c00 * id;
+  X[1] = (A[2] * A[7] - A[1] * A[8]) * id;
+  X[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+  X[3] = c01 * id;
+  X[4] = (A[0] * A[8] - A[2] * A[6]) * id;
+  X[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+  X[6] = c02 * id;
+  X[7] = (A[1] * A[6] - A[0] * A[7]) * id;
+  X[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+  return true;
+}
+
+// Per instance: Sinv = (K_bb - sum_q JL_q JL_q^T / LL_q)^-1 (3x3 Schur complement
+// of the loops' diagonal block).  status[i] = 1 when it is singular.
+__global__ void k_b_schur(const double* __restrict__ qsum, const int* __restrict__ inst_qoff, int n_inst,
+                          double* __restrict__ Sinv, double* __restrict__ ls) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  double S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int q = inst_qoff[i]; q < inst_qoff[i + 1]; ++q) {
+    const double* Q = qsum + 16 * (size_t)q;
+    const double il = 1.0 / Q[12];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) S[3 * a + b] += Q[3 * a + b] - Q[9 + a] * Q[9 + b] * il;
+  }
+  double X[9];
+  const bool ok = inv3(S, X);
+  for (int k = 0; k < 9; ++k) Sinv[9 * (size_t)i + k] = ok ? X[k] : 0.0;
+  if (!ok) ls[(size_t)i * kBatchLs + L_DONE] = -1.0;
+}
+
+// Per loop: cq = (sum_v J_v x_v (3), sum_v L_v . x_v).
+__global__ __launch_bounds__(256) void k_b_cx(const double* __restrict__ Jv, const double* __restrict__ Lv,
+                                              const int* __restrict__ chain_vert, const int* __restrict__ chain_voff,
+                                              const double* __restrict__ x, double* __restrict__ cq) {
+  __shared__ double sm[256];
+  const int q = blockIdx.x;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  for (int k = chain_voff[q] + threadIdx.x; k < chain_voff[q + 1]; k += 256) {
+    const int v = chain_vert[k];
+    const double* J = Jv + 9 * (size_t)v;
+    const double* L = Lv + 3 * (size_t)v;
+    const double x0 = x[3 * v], x1 = x[3 * v + 1], x2 = x[3 * v + 2];
+    a0 += J[0] * x0 + J[1] * x1 + J[2] * x2;
+    a1 += J[3] * x0 + J[4] * x1 + J[5] * x2;
+    a2 += J[6] * x0 + J[7] * x1 + J[8] * x2;
+    a3 += L[0] * x0 + L[1] * x1 + L[2] * x2;
+  }
+  a0 = block_sum(a0, sm);
+  a1 = block_sum(a1, sm);
+  a2 = block_sum(a2, sm);
+  a3 = block_sum(a3, sm);
+  if (threadIdx.x == 0) {
+    cq[4 * (size_t)q] = a0;
+    cq[4 * (size_t)q + 1] = a1;
+    cq[4 * (size_t)q + 2] = a2;
+    cq[4 * (size_t)q + 3] = a3;
+  }
+}
+
+// Per instance: y = (C C^T)^-1 w with w_b = sign * (sum_q cq[q].xyz) + eb and
+// w_q = sign * cq[q].w + eq (eb, eq optional extra right-hand sides).
+__global__ void k_b_ysolve(const double* __restrict__ qsum, const double* __restrict__ Sinv,
+                           const int* __restrict__ inst_qoff, int n_inst, const double* __restrict__ cq, double sign,
+                           const double* __restrict__ eb, const double* __restrict__ eq, double esign,
+                           double* __restrict__ yb, double* __restrict__ yq) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  double wb[3] = {0, 0, 0};
+  const int q0 = inst_qoff[i], q1 = inst_qoff[i + 1];
+  for (int q = q0; q < q1; ++q)
+    for (int a = 0; a < 3; ++a) wb[a] += cq ? sign * cq[4 * (size_t)q + a] : 0.0;
+  if (eb)
+    for (int a = 0; a < 3; ++a) wb[a] += esign * eb[3 * i + a];
+  // y_b = Sinv (w_b - sum_q JL_q w_q / LL_q)
+  double h[3] = {wb[0], wb[1], wb[2]};
+  for (int q = q0; q < q1; ++q) {
+    const double* Q = qsum + 16 * (size_t)q;
+    const double wq = (cq ? sign * cq[4 * (size_t)q + 3] : 0.0) + (eq ? esign * eq[q] : 0.0);
+    const double f = wq / Q[12];
+    for (int a = 0; a < 3; ++a) h[a] -= Q[9 + a] * f;
+  }
+  const double* S = Sinv + 9 * (size_t)i;
+  double y[3];
+  for (int a = 0; a < 3; ++a) {
+    y[a] = S[3 * a] * h[0] + S[3 * a + 1] * h[1] + S[3 * a + 2] * h[2];
+    yb[3 * i + a] = y[a];
+  }
+  // y_q = (w_q - JL_q . y_b) / LL_q
+  for (int q = q0; q < q1; ++q) {
+    const double* Q = qsum + 16 * (size_t)q;
+    const double wq = (cq ? sign * cq[4 * (size_t)q + 3] : 0.0) + (eq ? esign * eq[q] : 0.0);
+    yq[q] = (wq - (Q[9] * y[0] + Q[10] * y[1] + Q[11] * y[2])) / Q[12];
+  }
+}
+
+// out_v = (in_v or 0) - sgn (J_v^T y_b + L_v y_q), for vertices of instances
+// with mask[i] != 0 (all when mask is null); other vertices keep out.
+__global__ void k_b_apply_ct(const double* __restrict__ Jv, const double* __restrict__ Lv,
+                             const int* __restrict__ inst_of_vertex, const int* __restrict__ chain_of_vertex,
+                             const double* __restrict__ yb, const double* __restrict__ yq, const double* in,
+                             double sgn, int nV, double* out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nV) return;
+  const int i = inst_of_vertex[v], q = chain_of_vertex[v];
+  const double* J = Jv + 9 * (size_t)v;
+  const double* L = Lv + 3 * (size_t)v;
+  const double b0 = yb[3 * i], b1 = yb[3 * i + 1], b2 = yb[3 * i + 2], lq = yq[q];
+  for (int c = 0; c < 3; ++c) {
+    const double ct = J[c] * b0 + J[3 + c] * b1 + J[6 + c] * b2 + L[c] * lq;
+    out[3 * v + c] = (in ? in[3 * v + c] : 0.0) - sgn * ct;
+  }
+}
+
+// Phi of a trial curve (from its vertex positions): per loop
+// phiq = L0_q - sum l_I and bpart = sum l_I (x_I - x0) (summed per instance
+// by k_b_phi_inst).
+__global__ __launch_bounds__(256) void k_b_phi_loop(const double* __restrict__ gam, const int2* __restrict__ edges,
+                                                    const int* __restrict__ chain_edges,
+                                                    const int* __restrict__ chain_eoff,
+                                                    const int* __restrict__ chain_inst,
+                                                    const double* __restrict__ x0, const double* __restrict__ L0,
+                                                    double* __restrict__ phiq, double* __restrict__ cq) {
+  __shared__ double sm[256];
+  const int q = blockIdx.x;
+  const int i = chain_inst[q];
+  double l = 0, bx = 0, by = 0, bz = 0;
+  for (int k = chain_eoff[q] + threadIdx.x; k < chain_eoff[q + 1]; k += 256) {
+    const int2 e = edges[chain_edges[k]];
+    const double px = gam[3 * e.x], py = gam[3 * e.x + 1], pz = gam[3 * e.x + 2];
+    const double qx = gam[3 * e.y], qy = gam[3 * e.y + 1], qz = gam[3 * e.y + 2];
+    const double dx = qx - px, dy = qy - py, dz = qz - pz;
+    const double li = sqrt(dx * dx + dy * dy + dz * dz);
+    l += li;
+    bx += li * (0.5 * (px + qx) - x0[3 * i]);
+    by += li * (0.5 * (py + qy) - x0[3 * i + 1]);
+    bz += li * (0.5 * (pz + qz) - x0[3 * i + 2]);
+  }
+  l = block_sum(l, sm);
+  bx = block_sum(bx, sm);
+  by = block_sum(by, sm);
+  bz = block_sum(bz, sm);
+  if (threadIdx.x == 0) {
+    phiq[q] = L0[q] - l;
+    cq[4 * (size_t)q] = bx;
+    cq[4 * (size_t)q + 1] = by;
+    cq[4 * (size_t)q + 2] = bz;
+    cq[4 * (size_t)q + 3] = l;
+  }
+}
+
+// Per instance: phib = sum over loops of bpart; ls[L_PHI] = the largest
+// |Phi| relative to its scale (loop length for loops, L_i^2 for the barycenter).
+__global__ void k_b_phi_inst(const double* __restrict__ cq, const double* __restrict__ phiq,
+                             const double* __restrict__ L0, const int* __restrict__ inst_qoff, int n_inst,
+                             double* __restrict__ phib, double* __restrict__ ls) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  double b[3] = {0, 0, 0}, Li = 0, m = 0;
+  for (int q = inst_qoff[i]; q < inst_qoff[i + 1]; ++q) {
+    for (int a = 0; a < 3; ++a) b[a] += cq[4 * (size_t)q + a];
+    Li += L0[q];
+    m = fmax(m, fabs(phiq[q]) / L0[q]);
+  }
+  for (int a = 0; a < 3; ++a) {
+    phib[3 * i + a] = b[a];
+    m = fmax(m, fabs(b[a]) / (Li * Li));
+  }
+  ls[(size_t)i * kBatchLs + L_PHI] = m;
+}
+
+// Targets: x0_i = length-weighted barycenter, L0_q = loop length (from cq of
+// k_b_phi_loop run with x0 = 0 and L0 = 0).
+__global__ void k_b_targets(const double* __restrict__ cq, const int* __restrict__ inst_qoff, int n_inst,
+                            double* __restrict__ x0, double* __restrict__ L0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  double b[3] = {0, 0, 0}, Li = 0;
+  for (int q = inst_qoff[i]; q < inst_qoff[i + 1]; ++q) {
+    for (int a = 0; a < 3; ++a) b[a] += cq[4 * (size_t)q + a];
+    Li += cq[4 * (size_t)q + 3];
+    L0[q] = cq[4 * (size_t)q + 3];
+  }
+  for (int a = 0; a < 3; ++a) x0[3 * i + a] = b[a] / Li;
+}
+
+// ---------------------------------------------------------------------------
+// loop-block preconditioner
+// ---------------------------------------------------------------------------
+__global__ void k_b_dvec(const double* __restrict__ edge_out, const V4<double>* __restrict__ GA,
+                         const int* __restrict__ inc_off, const int* __restrict__ inc, int n,
+                         double* __restrict__ dvec) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  double d = 0.0;
+  for (int k = inc_off[v]; k < inc_off[v + 1]; ++k) {
+    const int I = inc[k] >> 1;
+    const double l = GA[I].w;
+    d += edge_out[8 * (size_t)I] / (2.0 * l) + l * edge_out[8 * (size_t)I + 1] / 16.0;
+  }
+  dvec[v] = d;
+}
+
+// Entry (a, b) of every loop block, one thread per entry of the flattened
+// blocks (the loop found by binary search over the block offsets).
+template <int EC>
+__global__ void k_b_blocks(const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB,
+                           const V4<double>* __restrict__ GT, const int2* __restrict__ edges,
+                           const int* __restrict__ inc_off, const int* __restrict__ inc,
+                           const double* __restrict__ edge_out, const double* __restrict__ dvec,
+                           const int* __restrict__ chain_vert, const int* __restrict__ chain_voff,
+                           const long long* __restrict__ blk_off, int nq, long long total, double half_expo,
+                           double* __restrict__ Minv) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= total) return;
+  int lo = 0, hi = nq - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (blk_off[mid] <= k) lo = mid;
+    else hi = mid - 1;
+  }
+  const int q = lo;
+  const int m = chain_voff[q + 1] - chain_voff[q];
+  const long long loc = k - blk_off[q];
+  const int a = (int)(loc / m), b = (int)(loc % m);
+  const int v = chain_vert[chain_voff[q] + a], w = chain_vert[chain_voff[q] + b];
+  double val;
+  if (v == w) val = dvec[v];
+  else val = sobolev_entry<double, EC>(min(v, w), max(v, w), GA, GB, GT, edges, inc_off, inc, edge_out, half_expo);
+  Minv[k] = val;
+}
+
+// In-place Gauss-Jordan inverse of every loop block (symmetric positive
+// definite: no pivoting), one workgroup per loop; col is scratch of the
+// loop's size.  For step k: scale row k by 1/M_kk (with M_kk replaced by 1),
+// then every other row i loses M_ik times row k (with M_ik replaced by 0).
+__global__ __launch_bounds__(256) void k_b_gauss_jordan(const int* __restrict__ chain_voff,
+                                                        const long long* __restrict__ blk_off,
+                                                        double* __restrict__ Minv, double* __restrict__ colbuf) {
+  const int q = blockIdx.x;
+  const int m = chain_voff[q + 1] - chain_voff[q];
+  double* M = Minv + blk_off[q];
+  double* f = colbuf + chain_voff[q];
+  for (int k = 0; k < m; ++k) {
+    const double piv = M[(size_t)k * m + k];
+    __syncthreads();
+    const double ip = 1.0 / piv;
+    for (int j = threadIdx.x; j < m; j += 256) {
+      const double val = (j == k) ? 1.0 : M[(size_t)k * m + j];
+      M[(size_t)k * m + j] = val * ip;
+    }
+    for (int i = threadIdx.x; i < m; i += 256) f[i] = (i == k) ? 0.0 : M[(size_t)i * m + k];
+    __syncthreads();
+    for (int i = 0; i < m; ++i) {
+      const double fi = f[i];
+      if (fi == 0.0) continue;
+      for (int j = threadIdx.x; j < m; j += 256) {
+        const double rk = M[(size_t)k * m + j];
+        M[(size_t)i * m + j] = (j == k) ? -fi * rk : M[(size_t)i * m + j] - fi * rk;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// z_v = sum_{w in loop(v)} Minv[v][w] r_w, one workgroup per loop, a wave per row.
+__global__ __launch_bounds__(256) void k_b_prec(const int* __restrict__ chain_vert, const int* __restrict__ chain_voff,
+                                                const long long* __restrict__ blk_off, const double* __restrict__ Minv,
+                                                const double* __restrict__ r, double* __restrict__ z) {
+  const int q = blockIdx.x;
+  const int m = chain_voff[q + 1] - chain_voff[q];
+  const int* vs = chain_vert + chain_voff[q];
+  const double* M = Minv + blk_off[q];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  for (int a = wave; a < m; a += 4) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int b = lane; b < m; b += 64) {
+      const double mv = M[(size_t)a * m + b];
+      const int w = vs[b];
+      s0 += mv * r[3 * w];
+      s1 += mv * r[3 * w + 1];
+      s2 += mv * r[3 * w + 2];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_down(s0, o);
+      s1 += __shfl_down(s1, o);
+      s2 += __shfl_down(s2, o);
+    }
+    if (lane == 0) {
+      const int v = vs[a];
+      z[3 * v] = s0;
+      z[3 * v + 1] = s1;
+      z[3 * v + 2] = s2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-instance PCG scalars and vector updates
+// ---------------------------------------------------------------------------
+__global__ void k_b_fill(double* __restrict__ x, size_t n, double v) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) x[k] = v;
+}
+
+__global__ void k_b_copy(const double* __restrict__ x, double* __restrict__ y, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) y[k] = x[k];
+}
+
+// PCG start: bb = <r, r>, active = (bb > 0), its = 0.
+__global__ void k_b_pcg_start(double* __restrict__ sc, int n_inst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  double* S = sc + (size_t)i * kBatchScal;
+  S[S_BB] = S[S_RR];
+  S[S_ACT] = S[S_BB] > 0.0 ? 1.0 : 0.0;
+  S[S_ITS] = 0.0;
+  S[S_RES] = S[S_BB] > 0.0 ? 1.0 : 0.0;
+}
+
+__global__ void k_b_pcg_alpha(double* __restrict__ sc, int n_inst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  double* S = sc + (size_t)i * kBatchScal;
+  const bool ok = S[S_ACT] > 0.0 && S[S_PQ] > 0.0;
+  if (S[S_ACT] > 0.0 && !(S[S_PQ] > 0.0)) S[S_ACT] = 0.0;  // breakdown: freeze
+  S[S_ALPHA] = ok ? S[S_RZ] / S[S_PQ] : 0.0;
+}
+
+// x += alpha p, r -= alpha q (active instances).
+__global__ void k_b_xr(const int* __restrict__ inst_of_vertex, const double* __restrict__ sc, int nV,
+                       const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ x,
+                       double* __restrict__ r) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * nV) return;
+  const double* S = sc + (size_t)inst_of_vertex[k / 3] * kBatchScal;
+  if (!(S[S_ACT] > 0.0)) return;
+  const double a = S[S_ALPHA];
+  x[k] += a * p[k];
+  r[k] -= a * q[k];
+}
+
+// After rr = <r,r> (slot S_RR) and rz' = <r,z> (slot S_BETA holds it on entry):
+// res = sqrt(rr / bb); converged instances are frozen; beta = rz' / rz.
+__global__ void k_b_pcg_beta(double* __restrict__ sc, int n_inst, double tol, int it) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  double* S = sc + (size_t)i * kBatchScal;
+  if (!(S[S_ACT] > 0.0)) return;
+  const double res = sqrt(fmax(S[S_RR], 0.0) / S[S_BB]);
+  S[S_RES] = res;
+  S[S_ITS] = it + 1;
+  const double rzn = S[S_BETA];
+  if (res < tol || !(rzn > 0.0)) {
+    S[S_ACT] = 0.0;
+    S[S_BETA] = 0.0;
+    return;
+  }
+  S[S_BETA] = rzn / S[S_RZ];
+  S[S_RZ] = rzn;
+}
+
+// p = z + beta p (active instances).
+__global__ void k_b_pupd(const int* __restrict__ inst_of_vertex, const double* __restrict__ sc, int nV,
+                         const double* __restrict__ z, double* __restrict__ p) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * nV) return;
+  const double* S = sc + (size_t)inst_of_vertex[k / 3] * kBatchScal;
+  if (!(S[S_ACT] > 0.0)) return;
+  p[k] = z[k] + S[S_BETA] * p[k];
+}
+
+__global__ void k_b_active_count(const double* __restrict__ sc, int n_inst, double* __restrict__ out) {
+  __shared__ double sm[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n_inst; i += 256) a += sc[(size_t)i * kBatchScal + S_ACT] > 0.0 ? 1.0 : 0.0;
+  a = block_sum(a, sm);
+  if (threadIdx.x == 0) out[0] = a;
+}
+
+// ---------------------------------------------------------------------------
+// line search
+// ---------------------------------------------------------------------------
+// ghat = g / |g|_i; ls: GN = |g|, SLOPE = <dE, ghat>, TAU = tau0, DONE = 0
+// (or -1 kept from a singular constraint system).
+__global__ void k_b_ls_init(double* __restrict__ ls, const double* __restrict__ sc, int n_inst, double tau0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  double* L = ls + (size_t)i * kBatchLs;
+  const double gn = sqrt(fmax(L[L_GN], 0.0));
+  L[L_GN] = gn;
+  L[L_SLOPE] = gn > 0.0 ? L[L_SLOPE] / gn : 0.0;
+  L[L_TAU] = tau0;
+  L[L_TAUACC] = 0.0;
+  L[L_BT] = 0.0;
+  L[L_RES] = sc[(size_t)i * kBatchScal + S_RES];
+  L[L_ITS] = sc[(size_t)i * kBatchScal + S_ITS];
+  if (L[L_DONE] != -1.0) L[L_DONE] = gn > 0.0 ? 0.0 : 1.0;
+}
+
+__global__ void k_b_ghat(const int* __restrict__ inst_of_vertex, const double* __restrict__ ls, int nV,
+                         const double* __restrict__ g, double* __restrict__ ghat) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * nV) return;
+  const double gn = ls[(size_t)inst_of_vertex[k / 3] * kBatchLs + L_GN];
+  ghat[k] = gn > 0.0 ? g[k] / gn : 0.0;
+}
+
+// E0 (and E1 = E0 until a step is accepted) from the per-instance energies.
+__global__ void k_b_set_e0(const double* __restrict__ energy, double* __restrict__ ls, int n_inst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  ls[(size_t)i * kBatchLs + L_E0] = energy[i];
+  ls[(size_t)i * kBatchLs + L_E1] = energy[i];
+}
+
+// trial = gamma - tau ghat for instances still searching.
+__global__ void k_b_trial(const int* __restrict__ inst_of_vertex, const double* __restrict__ ls, int nV,
+                          const double* __restrict__ gam, const double* __restrict__ ghat, double* __restrict__ trial) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * nV) return;
+  const double* L = ls + (size_t)inst_of_vertex[k / 3] * kBatchLs;
+  trial[k] = L[L_DONE] == 0.0 ? gam[k] - L[L_TAU] * ghat[k] : gam[k];
+}
+
+// trial += inc for instances still searching.
+__global__ void k_b_add_inc(const int* __restrict__ inst_of_vertex, const double* __restrict__ ls, int nV,
+                            const double* __restrict__ inc, double* __restrict__ trial) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * nV) return;
+  if (ls[(size_t)inst_of_vertex[k / 3] * kBatchLs + L_DONE] == 0.0) trial[k] += inc[k];
+}
+
+// Armijo (E1 <= E0 - c tau slope) and |Phi| <= accept_tol: accept, else halve tau.
+__global__ void k_b_accept(double* __restrict__ ls, const double* __restrict__ energy, int n_inst, double c_armijo,
+                           double accept_tol) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  double* L = ls + (size_t)i * kBatchLs;
+  if (L[L_DONE] != 0.0) return;
+  const double E1 = energy[i];
+  if (isfinite(E1) && E1 <= L[L_E0] - c_armijo * L[L_TAU] * L[L_SLOPE] && L[L_PHI] <= accept_tol) {
+    L[L_DONE] = 1.0;
+    L[L_E1] = E1;
+    L[L_TAUACC] = L[L_TAU];
+  } else {
+    L[L_TAU] *= 0.5;
+    L[L_BT] += 1.0;
+  }
+}
+
+// gamma = trial for instances that accepted in this round (DONE == 1 and the
+// accepted tau is the current one).
+__global__ void k_b_commit(const int* __restrict__ inst_of_vertex, const double* __restrict__ ls, int nV,
+                           const double* __restrict__ trial, double* __restrict__ gam, int round) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * nV) return;
+  const double* L = ls + (size_t)inst_of_vertex[k / 3] * kBatchLs;
+  if (L[L_DONE] == 1.0 && L[L_BT] == (double)round) gam[k] = trial[k];
+}
+
+// stats[i] = (E0, E1, tau, PCG iterations, PCG residual, status, |g|, backtracks)
+// status: 0 accepted, 1 no step found, 2 singular constraints.
+__global__ void k_b_stats(const double* __restrict__ ls, int n_inst, double* __restrict__ stats) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  const double* L = ls + (size_t)i * kBatchLs;
+  double* o = stats + 8 * (size_t)i;
+  o[0] = L[L_E0];
+  o[1] = L[L_DONE] == 1.0 ? L[L_E1] : L[L_E0];
+  o[2] = L[L_TAUACC];
+  o[3] = L[L_ITS];
+  o[4] = L[L_RES];
+  o[5] = L[L_DONE] == 1.0 ? 0.0 : (L[L_DONE] == -1.0 ? 2.0 : 1.0);
+  o[6] = L[L_GN];
+  o[7] = L[L_BT];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+rc_status batch_alloc(rc_ctx* c) {
+  Batch& B = c->batch;
+  const Curve& cv = c->curve;
+  if (!cv.chain) {
+    set_error("batch instances must be curve networks whose vertices have degree <= 2");
+    return RC_ERR_UNSUPPORTED;
+  }
+  const int nV = cv.nV, nE = cv.nE;
+  B.n_inst = cv.n_inst;
+  std::vector<Chain> chains = chains_of(cv);
+  B.nq = (int)chains.size();
+  std::vector<int> cvert, cvoff(1, 0), cof(nV, -1), cinst, cedges, ceoff(1, 0), qoff(B.n_inst + 1, 0);
+  std::vector<long long> boff(1, 0);
+  std::vector<int> vinst(nV);
+  for (int i = 0; i < B.n_inst; ++i)
+    for (int v = cv.h_inst_voff[i]; v < cv.h_inst_voff[i + 1]; ++v) vinst[v] = i;
+  int last_inst = -1;
+  for (int q = 0; q < B.nq; ++q) {
+    const Chain& ch = chains[q];
+    const int i = vinst[ch.verts[0]];
+    if (i < last_inst) {
+      set_error("batch loops out of instance order");
+      return RC_ERR_ARG;
+    }
+    last_inst = i;
+    for (int v : ch.verts) {
+      cvert.push_back(v);
+      cof[v] = q;
+    }
+    cvoff.push_back((int)cvert.size());
+    for (int I : ch.edges) cedges.push_back(I);
+    ceoff.push_back((int)cedges.size());
+    cinst.push_back(i);
+    qoff[i + 1]++;
+    const long long m = (long long)ch.verts.size();
+    boff.push_back(boff.back() + m * m);
+    B.max_chain = std::max(B.max_chain, (int)m);
+  }
+  for (int v = 0; v < nV; ++v)
+    if (cof[v] < 0) {
+      set_error("batch instances must not have isolated vertices");
+      return RC_ERR_ARG;
+    }
+  for (int i = 0; i < B.n_inst; ++i) {
+    if (qoff[i + 1] == 0) {
+      set_error("batch instance without a loop");
+      return RC_ERR_ARG;
+    }
+    qoff[i + 1] += qoff[i];
+  }
+  B.h_chain_voff = cvoff;
+  B.h_inst_qoff = qoff;
+  B.h_chain_eoff = ceoff;
+  B.blk_total = (size_t)boff.back();
+  RC_TRY(balloc(&B.chain_vert, nV));
+  RC_TRY(balloc(&B.chain_voff, B.nq + 1));
+  RC_TRY(balloc(&B.chain_of_vertex, nV));
+  RC_TRY(balloc(&B.chain_inst, B.nq));
+  RC_TRY(balloc(&B.inst_qoff, B.n_inst + 1));
+  RC_TRY(balloc(&B.chain_eoff, B.nq + 1));
+  RC_TRY(balloc(&B.chain_edges, nE));
+  RC_TRY(balloc(&B.blk_off, B.nq + 1));
+  RC_HIP(hipMemcpy(B.chain_vert, cvert.data(), sizeof(int) * nV, hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(B.chain_voff, cvoff.data(), sizeof(int) * (B.nq + 1), hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(B.chain_of_vertex, cof.data(), sizeof(int) * nV, hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(B.chain_inst, cinst.data(), sizeof(int) * B.nq, hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(B.inst_qoff, qoff.data(), sizeof(int) * (B.n_inst + 1), hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(B.chain_eoff, ceoff.data(), sizeof(int) * (B.nq + 1), hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(B.chain_edges, cedges.data(), sizeof(int) * nE, hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(B.blk_off, boff.data(), sizeof(long long) * (B.nq + 1), hipMemcpyHostToDevice));
+  const size_t n3 = 3 * (size_t)nV;
+  RC_TRY(balloc(&B.Minv, B.blk_total));
+  RC_TRY(balloc(&B.gj_col, nV));
+  RC_TRY(balloc(&B.x0, 3 * (size_t)B.n_inst));
+  RC_TRY(balloc(&B.L0, B.nq));
+  RC_TRY(balloc(&B.Jv, 9 * (size_t)nV));
+  RC_TRY(balloc(&B.Lv, 3 * (size_t)nV));
+  RC_TRY(balloc(&B.qsum, 16 * (size_t)B.nq));
+  RC_TRY(balloc(&B.Sinv, 9 * (size_t)B.n_inst));
+  RC_TRY(balloc(&B.cq, 4 * (size_t)B.nq));
+  RC_TRY(balloc(&B.yb, 3 * (size_t)B.n_inst));
+  RC_TRY(balloc(&B.yq, B.nq));
+  RC_TRY(balloc(&B.dvec, nV));
+  double** vecs[] = {&B.x, &B.r, &B.z, &B.p, &B.q, &B.b, &B.t, &B.trial, &B.ghat, &B.dE, &B.g, &B.inc};
+  for (double** v : vecs) RC_TRY(balloc(v, n3));
+  RC_TRY(balloc(&B.sc, (size_t)kBatchScal * B.n_inst));
+  RC_TRY(balloc(&B.ls, (size_t)kBatchLs * B.n_inst));
+  RC_TRY(balloc(&B.energy, B.n_inst));
+  RC_TRY(balloc(&B.stats, 8 * (size_t)B.n_inst + 8));
+  RC_TRY(balloc(&B.phiq, B.nq));
+  RC_TRY(balloc(&B.phib, 3 * (size_t)B.n_inst));
+  RC_HIP(hipMemset(B.ls, 0, sizeof(double) * kBatchLs * B.n_inst));
+  RC_HIP(hipMemset(B.sc, 0, sizeof(double) * kBatchScal * B.n_inst));
+  return RC_OK;
+}
+
+void batch_free(rc_ctx* c) {
+  Batch& B = c->batch;
+  if (B.exec) hipGraphExecDestroy(B.exec);
+  if (B.graph) hipGraphDestroy(B.graph);
+  if (B.cap_stream) hipStreamDestroy(B.cap_stream);
+  void* ps[] = {B.chain_vert, B.chain_voff, B.chain_of_vertex, B.chain_inst, B.inst_qoff, B.chain_eoff,
+                B.chain_edges, B.blk_off, B.Minv, B.gj_col, B.x0, B.L0, B.Jv, B.Lv, B.qsum, B.Sinv, B.cq,
+                B.yb, B.yq, B.dvec, B.x, B.r, B.z, B.p, B.q, B.b, B.t, B.trial, B.ghat, B.dE, B.g, B.inc,
+                B.sc, B.ls, B.energy, B.stats, B.phiq, B.phib};
+  for (void* p : ps)
+    if (p) hipFree(p);
+  B = Batch();
+}
+
+rc_status batch_edge_sums(rc_ctx* c, int slot, double* out) {
+  hipLaunchKernelGGL(k_b_edge_sum, dim3(c->curve.n_inst), dim3(256), 0, c->stream, c->curve.edge_out, slot,
+                     c->curve.inst_eoff, out);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+// x0 and L0 from gamma_ref (the constraint targets).
+rc_status batch_set_constraints(rc_ctx* c, const double* gamma_ref) {
+  Batch& B = c->batch;
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(k_b_fill, dim3(cdiv(3 * B.n_inst, 256)), dim3(256), 0, s, B.x0, (size_t)3 * B.n_inst, 0.0);
+  hipLaunchKernelGGL(k_b_fill, dim3(cdiv(B.nq, 256)), dim3(256), 0, s, B.L0, (size_t)B.nq, 0.0);
+  hipLaunchKernelGGL(k_b_phi_loop, dim3(B.nq), dim3(256), 0, s, gamma_ref, c->curve.edges, B.chain_edges,
+                     B.chain_eoff, B.chain_inst, B.x0, B.L0, B.phiq, B.cq);
+  hipLaunchKernelGGL(k_b_targets, dim3(cdiv(B.n_inst, 64)), dim3(64), 0, s, B.cq, B.inst_qoff, B.n_inst, B.x0, B.L0);
+  RC_HIP(hipGetLastError());
+  RC_HIP(hipStreamSynchronize(s));
+  B.ready = true;
+  return RC_OK;
+}
+
+// out = P in (in may equal out) with the constraints frozen at the last prepare.
+static void b_project(rc_ctx* c, const double* in, double* out) {
+  Batch& B = c->batch;
+  hipStream_t s = c->stream;
+  const int nV = c->nV;
+  hipLaunchKernelGGL(k_b_cx, dim3(B.nq), dim3(256), 0, s, B.Jv, B.Lv, B.chain_vert, B.chain_voff, in, B.cq);
+  hipLaunchKernelGGL(k_b_ysolve, dim3(cdiv(B.n_inst, 64)), dim3(64), 0, s, B.qsum, B.Sinv, B.inst_qoff, B.n_inst,
+                     (const double*)B.cq, 1.0, (const double*)nullptr, (const double*)nullptr, 0.0, B.yb, B.yq);
+  hipLaunchKernelGGL(k_b_apply_ct, dim3(cdiv(nV, 256)), dim3(256), 0, s, B.Jv, B.Lv, c->curve.inst_of_vertex,
+                     B.chain_of_vertex, B.yb, B.yq, in, 1.0, nV, out);
+}
+
+// Constraint rows at gamma (geometry loaded) and the loop-block preconditioner.
+static rc_status b_prepare(rc_ctx* c) {
+  Batch& B = c->batch;
+  const Curve& cv = c->curve;
+  hipStream_t s = c->stream;
+  const int nV = c->nV;
+  hipLaunchKernelGGL(k_b_rows, dim3(cdiv(nV, 256)), dim3(256), 0, s, cv.gd.a, cv.gd.b, cv.gd.t, cv.inc_off, cv.inc,
+                     cv.inst_of_vertex, B.x0, nV, B.Jv, B.Lv);
+  hipLaunchKernelGGL(k_b_qsum, dim3(B.nq), dim3(256), 0, s, B.Jv, B.Lv, B.chain_vert, B.chain_voff, B.qsum);
+  hipLaunchKernelGGL(k_b_schur, dim3(cdiv(B.n_inst, 64)), dim3(64), 0, s, B.qsum, B.inst_qoff, B.n_inst, B.Sinv,
+                     B.ls);
+  // per-edge sums Wq, P0 in FP32 (the preconditioner's diagonal), the loop blocks in FP64
+  RC_TRY(launch_edge_sums(cv, c->alpha, c->beta, RC_F32, s));
+  hipLaunchKernelGGL(k_b_dvec, dim3(cdiv(nV, 256)), dim3(256), 0, s, cv.edge_out, cv.gd.a, cv.inc_off, cv.inc, nV,
+                     B.dvec);
+  const double sg = (c->beta - 1.0) / c->alpha - 1.0;
+  const double half_expo = 0.5 * (2.0 * sg + 1.0);
+  const long long tot = (long long)B.blk_total;
+  const int nb = (int)((tot + 255) / 256);
+#define RC_BLK(EC)                                                                                                \
+  hipLaunchKernelGGL((k_b_blocks<EC>), dim3(nb), dim3(256), 0, s, cv.gd.a, cv.gd.b, cv.gd.t, cv.edges, cv.inc_off, \
+                     cv.inc, cv.edge_out, B.dvec, B.chain_vert, B.chain_voff, B.blk_off, B.nq, tot, half_expo,     \
+                     B.Minv)
+  switch (exp_case(c->alpha, c->beta)) {
+    case kA2B4: RC_BLK(kA2B4); break;
+    case kA2B45: RC_BLK(kA2B45); break;
+    default: RC_BLK(kGeneral); break;
+  }
+#undef RC_BLK
+  hipLaunchKernelGGL(k_b_gauss_jordan, dim3(B.nq), dim3(256), 0, s, B.chain_voff, B.blk_off, B.Minv, B.gj_col);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+// z = P M^-1 P r (r already in range P).
+static void b_precondition(rc_ctx* c, const double* r, double* z) {
+  Batch& B = c->batch;
+  hipLaunchKernelGGL(k_b_prec, dim3(B.nq), dim3(256), 0, c->stream, B.chain_vert, B.chain_voff, B.blk_off, B.Minv, r,
+                     z);
+  b_project(c, z, z);
+}
+
+// q = P Abar p (FP32 operator, geometry of the prepared curve loaded).
+static rc_status b_operator(rc_ctx* c, const double* p, double* q) {
+  RC_TRY(launch_sobolev(c->curve, c->alpha, c->beta, RC_F32, p, q, nullptr, c->stream));
+  b_project(c, q, q);
+  return RC_OK;
+}
+
+// Projected PCG on every instance: x = (P Abar P)^+ P rhs, to the relative
+// residual tol or max_it iterations.  check_every > 0 (never while
+// capturing): stop once no instance is active, checked on the host.
+static rc_status b_pcg(rc_ctx* c, const double* rhs, double* x, double tol, int max_it, int check_every) {
+  Batch& B = c->batch;
+  hipStream_t s = c->stream;
+  const int nV = c->nV, n3 = 3 * nV;
+  const dim3 gv(cdiv(n3, 256)), gi(cdiv(B.n_inst, 64)), bi(64), bv(256);
+  const int* vo = c->curve.inst_voff;
+  const int* iv = c->curve.inst_of_vertex;
+  b_project(c, rhs, B.r);
+  hipLaunchKernelGGL(k_b_fill, gv, bv, 0, s, x, (size_t)n3, 0.0);
+  hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.r, B.r, vo, B.sc, kBatchScal, (int)S_RR);
+  hipLaunchKernelGGL(k_b_pcg_start, gi, bi, 0, s, B.sc, B.n_inst);
+  b_precondition(c, B.r, B.z);
+  hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.r, B.z, vo, B.sc, kBatchScal, (int)S_RZ);
+  hipLaunchKernelGGL(k_b_copy, gv, bv, 0, s, B.z, B.p, n3);
+  for (int it = 0; it < max_it; ++it) {
+    RC_TRY(b_operator(c, B.p, B.q));
+    hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.p, B.q, vo, B.sc, kBatchScal, (int)S_PQ);
+    hipLaunchKernelGGL(k_b_pcg_alpha, gi, bi, 0, s, B.sc, B.n_inst);
+    hipLaunchKernelGGL(k_b_xr, gv, bv, 0, s, iv, B.sc, nV, B.p, B.q, x, B.r);
+    b_precondition(c, B.r, B.z);
+    hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.r, B.r, vo, B.sc, kBatchScal, (int)S_RR);
+    hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.r, B.z, vo, B.sc, kBatchScal, (int)S_BETA);
+    hipLaunchKernelGGL(k_b_pcg_beta, gi, bi, 0, s, B.sc, B.n_inst, tol, it);
+    hipLaunchKernelGGL(k_b_pupd, gv, bv, 0, s, iv, B.sc, nV, B.z, B.p);
+    if (check_every > 0 && (it + 1) % check_every == 0) {
+      hipLaunchKernelGGL(k_b_active_count, dim3(1), dim3(256), 0, s, B.sc, B.n_inst, B.stats + 8 * (size_t)B.n_inst);
+      double act = 0.0;
+      RC_HIP(hipMemcpyAsync(&act, B.stats + 8 * (size_t)B.n_inst, sizeof(double), hipMemcpyDeviceToHost, s));
+      RC_HIP(hipStreamSynchronize(s));
+      if (act == 0.0) break;
+    }
+  }
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+rc_status batch_gradient(rc_ctx* c, const double* gamma, const double* dE, double* g, const rc_batch_opts& o) {
+  if (!c->batch.ready) {
+    set_error("batch constraints not set (rc_batch_set_constraints)");
+    return RC_ERR_ARG;
+  }
+  RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));
+  RC_TRY(b_prepare(c));
+  return b_pcg(c, dE, g, o.tol, o.max_iter, o.check_every);
+}
+
+// The whole step on the context stream, without host synchronisation when
+// check_every == 0.  gamma is updated in place per instance.
+static rc_status b_step(rc_ctx* c, double* gamma, const rc_batch_opts& o, int check_every) {
+  Batch& B = c->batch;
+  Curve& cv = c->curve;
+  hipStream_t s = c->stream;
+  const int nV = c->nV, n3 = 3 * nV;
+  const dim3 gv(cdiv(n3, 256)), gi(cdiv(B.n_inst, 64)), bi(64), bv(256);
+  const int* vo = cv.inst_voff;
+  const int* iv = cv.inst_of_vertex;
+  // energy and differential (with the obstacle), per-instance energies
+  RC_TRY(launch_geometry(cv, gamma, RC_F32, s));
+  RC_TRY(launch_tpe(cv, c->alpha, c->beta, RC_F32, true, nullptr, B.dE, s));
+  hipLaunchKernelGGL(k_b_edge_sum, dim3(B.n_inst), bv, 0, s, cv.edge_out, 0, cv.inst_eoff, B.energy);
+  // L_DONE must be reset before k_b_schur may flag singular systems
+  hipLaunchKernelGGL(k_b_fill, dim3(cdiv(kBatchLs * B.n_inst, 256)), bv, 0, s, B.ls, (size_t)kBatchLs * B.n_inst, 0.0);
+  // constraints and preconditioner at gamma, projected gradient
+  RC_TRY(b_prepare(c));
+  RC_TRY(b_pcg(c, B.dE, B.g, o.tol, o.max_iter, check_every));
+  // per-instance line search
+  hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.g, B.g, vo, B.ls, kBatchLs, (int)L_GN);
+  hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.dE, B.g, vo, B.ls, kBatchLs, (int)L_SLOPE);
+  hipLaunchKernelGGL(k_b_ls_init, gi, bi, 0, s, B.ls, B.sc, B.n_inst, o.tau0);
+  hipLaunchKernelGGL(k_b_ghat, gv, bv, 0, s, iv, B.ls, nV, B.g, B.ghat);
+  hipLaunchKernelGGL(k_b_set_e0, gi, bi, 0, s, B.energy, B.ls, B.n_inst);
+  for (int round = 0; round < o.ls_rounds; ++round) {
+    hipLaunchKernelGGL(k_b_trial, gv, bv, 0, s, iv, B.ls, nV, gamma, B.ghat, B.trial);
+    for (int k = 0; k < o.proj_iters; ++k) {
+      // Phi(trial), z = C^T (C C^T)^-1 (-Phi) with C at gamma, then the A-orthogonal correction
+      hipLaunchKernelGGL(k_b_phi_loop, dim3(B.nq), bv, 0, s, B.trial, cv.edges, B.chain_edges, B.chain_eoff,
+                         B.chain_inst, B.x0, B.L0, B.phiq, B.cq);
+      hipLaunchKernelGGL(k_b_phi_inst, gi, bi, 0, s, B.cq, B.phiq, B.L0, B.inst_qoff, B.n_inst, B.phib, B.ls);
+      hipLaunchKernelGGL(k_b_ysolve, gi, bi, 0, s, B.qsum, B.Sinv, B.inst_qoff, B.n_inst, (const double*)nullptr, 0.0,
+                         (const double*)B.phib, (const double*)B.phiq, -1.0, B.yb, B.yq);
+      hipLaunchKernelGGL(k_b_apply_ct, dim3(cdiv(nV, 256)), bv, 0, s, B.Jv, B.Lv, iv, B.chain_of_vertex, B.yb, B.yq,
+                         (const double*)nullptr, -1.0, nV, B.inc);
+      // y = (P A P)^+ P A z, increment = z - y
+      RC_TRY(launch_sobolev(cv, c->alpha, c->beta, RC_F32, B.inc, B.b, nullptr, s));
+      RC_TRY(b_pcg(c, B.b, B.t, o.proj_tol, o.proj_max_iter, 0));
+      vec_axpby(-1.0, B.t, 1.0, B.inc, n3, s);
+      hipLaunchKernelGGL(k_b_add_inc, gv, bv, 0, s, iv, B.ls, nV, B.inc, B.trial);
+    }
+    // constraint violation and energy at the trial curves
+    hipLaunchKernelGGL(k_b_phi_loop, dim3(B.nq), bv, 0, s, B.trial, cv.edges, B.chain_edges, B.chain_eoff,
+                       B.chain_inst, B.x0, B.L0, B.phiq, B.cq);
+    hipLaunchKernelGGL(k_b_phi_inst, gi, bi, 0, s, B.cq, B.phiq, B.L0, B.inst_qoff, B.n_inst, B.phib, B.ls);
+    RC_TRY(launch_geometry(cv, B.trial, RC_F32, s));
+    RC_TRY(launch_tpe(cv, c->alpha, c->beta, RC_F32, false, nullptr, nullptr, s));
+    hipLaunchKernelGGL(k_b_edge_sum, dim3(B.n_inst), bv, 0, s, cv.edge_out, 0, cv.inst_eoff, B.energy);
+    hipLaunchKernelGGL(k_b_accept, gi, bi, 0, s, B.ls, B.energy, B.n_inst, o.c_armijo, o.accept_tol);
+    hipLaunchKernelGGL(k_b_commit, gv, bv, 0, s, iv, B.ls, nV, B.trial, gamma, round);
+    // the operator of the next round is again the one at gamma
+    if (round + 1 < o.ls_rounds) RC_TRY(launch_geometry(cv, gamma, RC_F32, s));
+  }
+  hipLaunchKernelGGL(k_b_stats, gi, bi, 0, s, B.ls, B.n_inst, B.stats);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+rc_status batch_step(rc_ctx* c, double* gamma, const rc_batch_opts& o, double* stats_h) {
+  Batch& B = c->batch;
+  if (!B.ready) {
+    set_error("batch constraints not set (rc_batch_set_constraints)");
+    return RC_ERR_ARG;
+  }
+  if (o.graph) {
+    const bool same = B.captured && B.cap_gamma == gamma && std::memcmp(&B.cap_opts, &o, sizeof(o)) == 0;
+    if (!same) {
+      if (B.exec) hipGraphExecDestroy(B.exec);
+      if (B.graph) hipGraphDestroy(B.graph);
+      B.exec = nullptr;
+      B.graph = nullptr;
+      B.captured = false;
+      if (!B.cap_stream) RC_HIP(hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking));
+      RC_HIP(hipStreamSynchronize(c->stream));
+      hipStream_t keep = c->stream;
+      KernelTimer* keep_timer = c->curve.timer;
+      c->stream = B.cap_stream;
+      c->curve.timer = nullptr;  // no event records inside the graph
+      RC_HIP(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal));
+      rc_status st = b_step(c, gamma, o, 0);
+      hipGraph_t gr = nullptr;
+      hipError_t ce = hipStreamEndCapture(B.cap_stream, &gr);
+      c->stream = keep;
+      c->curve.timer = keep_timer;
+      if (st != RC_OK) {
+        if (gr) hipGraphDestroy(gr);
+        return st;
+      }
+      if (ce != hipSuccess) {
+        set_error(std::string("batch step capture failed: ") + hipGetErrorString(ce));
+        return RC_ERR_HIP;
+      }
+      B.graph = gr;
+      RC_HIP(hipGraphInstantiate(&B.exec, gr, nullptr, nullptr, 0));
+      B.captured = true;
+      B.cap_opts = o;
+      B.cap_gamma = gamma;
+    }
+    RC_HIP(hipGraphLaunch(B.exec, c->stream));
+  } else {
+    RC_TRY(b_step(c, gamma, o, o.check_every));
+  }
+  if (stats_h) {
+    RC_HIP(hipMemcpyAsync(stats_h, B.stats, sizeof(double) * 8 * B.n_inst, hipMemcpyDeviceToHost, c->stream));
+    RC_HIP(hipStreamSynchronize(c->stream));
+  }
+  return RC_OK;
+}
+
+}  // namespace rc

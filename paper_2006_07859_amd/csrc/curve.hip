@@ -2,6 +2,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <string>
 
 #include "rc_internal.h"
 
@@ -110,6 +111,7 @@ rc_status Curve::init(int nV_, int nE_, const int* edges_h) {
   }
   const int slots = std::max(kTpeSlots, std::max(kSobSlots, 10));
   RC_TRY(dmalloc(&part, (size_t)(nchunk + 1) * slots * nE));  // + one chunk for the FP64 near band
+  part_chunks = nchunk + 1;
   RC_TRY(dmalloc(&edge_out, 8 * (size_t)nE));
   RC_TRY(dmalloc(&red, 256));
   // chain position of every edge: near pairs along a chain are evaluated in FP64
@@ -133,11 +135,127 @@ rc_status Curve::init(int nV_, int nE_, const int* edges_h) {
   return RC_OK;
 }
 
+rc_status Curve::set_instances(int n_inst_, const int* voff_h) {
+  if (n_inst_ < 1) {
+    set_error("a batch needs at least one instance");
+    return RC_ERR_ARG;
+  }
+  h_inst_voff.assign(voff_h, voff_h + n_inst_ + 1);
+  if (h_inst_voff[0] != 0 || h_inst_voff[n_inst_] != nV) {
+    set_error("instance vertex offsets must start at 0 and end at the vertex count");
+    return RC_ERR_ARG;
+  }
+  for (int i = 0; i < n_inst_; ++i)
+    if (h_inst_voff[i + 1] <= h_inst_voff[i]) {
+      set_error("instance vertex offsets must increase");
+      return RC_ERR_ARG;
+    }
+  // edges must be grouped by instance, in instance order, and stay inside it
+  std::vector<int> vinst(nV);
+  for (int i = 0; i < n_inst_; ++i)
+    for (int v = h_inst_voff[i]; v < h_inst_voff[i + 1]; ++v) vinst[v] = i;
+  std::vector<int> einst(nE);
+  h_inst_eoff.assign(n_inst_ + 1, 0);
+  for (int I = 0; I < nE; ++I) {
+    const int a = vinst[h_edges[2 * I]], b = vinst[h_edges[2 * I + 1]];
+    if (a != b) {
+      set_error("edge " + std::to_string(I) + " joins two instances");
+      return RC_ERR_ARG;
+    }
+    if (I > 0 && a < einst[I - 1]) {
+      set_error("edges must be grouped by instance in instance order");
+      return RC_ERR_ARG;
+    }
+    einst[I] = a;
+    h_inst_eoff[a + 1]++;
+  }
+  for (int i = 0; i < n_inst_; ++i) {
+    if (h_inst_eoff[i + 1] == 0) {
+      set_error("instance " + std::to_string(i) + " has no edges");
+      return RC_ERR_ARG;
+    }
+    h_inst_eoff[i + 1] += h_inst_eoff[i];
+  }
+  n_inst = n_inst_;
+  RC_TRY(dmalloc(&inst_voff, n_inst + 1));
+  RC_TRY(dmalloc(&inst_eoff, n_inst + 1));
+  RC_TRY(dmalloc(&inst_of_edge, nE));
+  RC_TRY(dmalloc(&inst_of_vertex, nV));
+  RC_TRY(dmalloc(&nch_e, nE));
+  RC_TRY(dmalloc(&counter, 4));
+  RC_HIP(hipMemcpy(inst_voff, h_inst_voff.data(), sizeof(int) * (n_inst + 1), hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(inst_eoff, h_inst_eoff.data(), sizeof(int) * (n_inst + 1), hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(inst_of_edge, einst.data(), sizeof(int) * nE, hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(inst_of_vertex, vinst.data(), sizeof(int) * nV, hipMemcpyHostToDevice));
+  return build_items(1024, 8);
+}
+
+// Work items of the batch pair kernels for source chunks of src_chunk edges;
+// blocks_per_cu_ workgroups per compute unit in the persistent launches.
+rc_status Curve::build_items(int src_chunk, int blocks_per_cu_) {
+  if (src_chunk < kTile || src_chunk > (1 << 20) || blocks_per_cu_ < 1 || blocks_per_cu_ > 32) {
+    set_error("batch tiling out of range");
+    return RC_ERR_ARG;
+  }
+  struct It {
+    int4 w;
+    long long cost;
+  };
+  std::vector<It> list;
+  std::vector<int> nch(nE);
+  int nmax = 1;
+  for (int i = 0; i < n_inst; ++i) {
+    const int e0 = h_inst_eoff[i], e1 = h_inst_eoff[i + 1];
+    const int nc = (e1 - e0 + src_chunk - 1) / src_chunk;
+    if (nc >= (1 << 15)) {
+      set_error("instance too large for the batch tiling");
+      return RC_ERR_ARG;
+    }
+    nmax = std::max(nmax, nc);
+    for (int I = e0; I < e1; ++I) nch[I] = nc;
+    for (int t0 = e0; t0 < e1; t0 += kTile) {
+      const int tc = std::min(kTile, e1 - t0);
+      for (int c = 0; c < nc; ++c) {
+        const int s0 = e0 + c * src_chunk, s1 = std::min(e1, s0 + src_chunk);
+        list.push_back({make_int4(t0, s0, s1, (c << 16) | tc), (long long)tc * (s1 - s0)});
+      }
+    }
+  }
+  std::stable_sort(list.begin(), list.end(), [](const It& a, const It& b) { return a.cost > b.cost; });
+  std::vector<int4> h(list.size());
+  for (size_t k = 0; k < list.size(); ++k) h[k] = list[k].w;
+  if (items) hipFree(items);
+  items = nullptr;
+  n_items = (int)h.size();
+  RC_TRY(dmalloc(&items, std::max<size_t>(h.size(), 1)));
+  RC_HIP(hipMemcpy(items, h.data(), sizeof(int4) * h.size(), hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(nch_e, nch.data(), sizeof(int) * nE, hipMemcpyHostToDevice));
+  nchunk = nmax;
+  item_src = src_chunk;
+  if (part_chunks < nchunk + 1) {
+    hipFree(part);
+    part = nullptr;
+    const int slots = std::max(kTpeSlots, std::max(kSobSlots, 10));
+    RC_TRY(dmalloc(&part, (size_t)(nchunk + 1) * slots * nE));
+    part_chunks = nchunk + 1;
+  }
+  int dev = 0, ncu = 0;
+  RC_HIP(hipGetDevice(&dev));
+  RC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  blocks_per_cu = blocks_per_cu_;
+  persist_blocks = std::max(1, ncu * blocks_per_cu);
+  return RC_OK;
+}
+
 void Curve::release() {
   void* ptrs[] = {edges, inc_off, inc, gf.a, gf.b, gf.t, gd.a, gd.b, gd.t,
-                  rhs_f[0], rhs_f[1], rhs_d[0], rhs_d[1], part, edge_out, red, cinfo, chain_edge};
+                  rhs_f[0], rhs_f[1], rhs_d[0], rhs_d[1], part, edge_out, red, cinfo, chain_edge,
+                  inst_voff, inst_eoff, inst_of_edge, inst_of_vertex, items, nch_e, counter};
   for (void* p : ptrs)
     if (p) hipFree(p);
+  inst_voff = inst_eoff = inst_of_edge = inst_of_vertex = nch_e = counter = nullptr;
+  items = nullptr;
+  n_inst = n_items = 0;
   edges = nullptr;
   inc_off = inc = nullptr;
   gf = EdgeGeom<float>();

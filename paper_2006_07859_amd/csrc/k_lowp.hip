@@ -87,61 +87,6 @@ __device__ __forceinline__ int chain_offset(int4 a, int4 b) {
   return d;
 }
 
-// Off-diagonal entry A_vw (v != w) evaluated in precision R from the FP64
-// geometry: coordinate differences are taken in FP64 and then rounded, so an
-// FP32 entry carries a few ulps of error even for vertices close together
-// (differences of rounded coordinates would lose bits in proportion to
-// |x| / |x_v - x_w|).
-template <typename R, int EC>
-__device__ __forceinline__ R lowp_entry(int v, int w, const V4<double>* __restrict__ GA,
-                                        const V4<double>* __restrict__ GB, const V4<double>* __restrict__ GT,
-                                        const int2* __restrict__ edges, const int* __restrict__ inc_off,
-                                        const int* __restrict__ inc, const double* __restrict__ edge_out,
-                                        R half_expo) {
-  R acc = R(0);
-  const int kw0 = inc_off[w], kw1 = inc_off[w + 1];
-  for (int kv = inc_off[v]; kv < inc_off[v + 1]; ++kv) {
-    const int I = inc[kv] >> 1;
-    const R sv = (inc[kv] & 1) ? R(1) : R(-1);
-    const int2 ei = edges[I];
-    const V4<double> ia = GA[I], ib = GB[I], tid = GT[I];
-    const R tix = (R)tid.x, tiy = (R)tid.y, tiz = (R)tid.z, li = (R)ia.w;
-    for (int kw = kw0; kw < kw1; ++kw) {
-      const int J = inc[kw] >> 1;
-      if (I == J) {
-        const double* o = edge_out + 8 * (size_t)I;  // (Wq, P0) in slots 0, 1
-        const double l = ia.w;
-        acc += (R)(-o[0] / (2.0 * l) + l * o[1] / 16.0);
-        continue;
-      }
-      const int2 ej = edges[J];
-      if (ei.x == ej.x || ei.x == ej.y || ei.y == ej.x || ei.y == ej.y) continue;
-      const R sw = (inc[kw] & 1) ? R(1) : R(-1);
-      const V4<double> ja = GA[J], jb = GB[J], tjd = GT[J];
-      const R tjx = (R)tjd.x, tjy = (R)tjd.y, tjz = (R)tjd.z;
-      R rho = R(0), rho0 = R(0);
-      const V4<double>* P[2] = {&ia, &ib};
-      const V4<double>* Q[2] = {&ja, &jb};
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          const R dx = (R)(P[x]->x - Q[y]->x), dy = (R)(P[x]->y - Q[y]->y), dz = (R)(P[x]->z - Q[y]->z);
-          const R r2 = dx * dx + dy * dy + dz * dz;
-          const R rs = f_rsq<R>(r2), ri = rs * rs;
-          const R p = pow_sigma<EC, R>(r2, rs, ri, half_expo);
-          const R cI = cross_norm2<R>(tix, tiy, tiz, dx, dy, dz);
-          const R cJ = cross_norm2<R>(tjx, tjy, tjz, dx, dy, dz);
-          rho += p;
-          rho0 += p * (cI + cJ) * ri * ri;
-        }
-      const R tt = tix * tjx + tiy * tjy + tiz * tjz;
-      acc += R(-0.5) * sv * sw * rho * tt - R(0.0625) * li * (R)ja.w * rho0;
-    }
-  }
-  return acc;
-}
-
 // d_v and sqrt(d_v) from the FP64 per-edge sums.
 __global__ void k_lowp_dvec(const double* __restrict__ edge_out, const V4<double>* __restrict__ GA,
                             const int* __restrict__ inc_off, const int* __restrict__ inc, int n,
@@ -192,7 +137,7 @@ __global__ __launch_bounds__(256) void k_assemble_lowp(
         const int off = chain_offset(iv, vinfo[w]);
         if (off < -band || off > band) {
           // evaluated with the smaller index first, so that S^ is exactly symmetric
-          const float a = lowp_entry<float, EC>(min(v, w), max(v, w), GA, GB, GT, edges, inc_off, inc, edge_out,
+          const float a = sobolev_entry<float, EC>(min(v, w), max(v, w), GA, GB, GT, edges, inc_off, inc, edge_out,
                                                 half_expo);
           const double sw = sqd[w];
           sf = (float)((double)a / (sv * sw));
@@ -249,7 +194,7 @@ __global__ void k_lowp_band(const V4<double>* __restrict__ GA, const V4<double>*
     float val = 0.f;
     if (w >= 0) {
       const double a =
-          lowp_entry<double, EC>(min(v, w), max(v, w), GA, GB, GT, edges, inc_off, inc, edge_out, half_expo);
+          sobolev_entry<double, EC>(min(v, w), max(v, w), GA, GB, GT, edges, inc_off, inc, edge_out, half_expo);
       val = (float)(a / (sqd[v] * sqd[w]));
       rs += (double)val * sqd[w];
     }

@@ -61,18 +61,24 @@ __device__ __forceinline__ bool chain_near(int4 ci, int4 cj) {
 // that are chain-near (which include every pair sharing a vertex) are left
 // to the FP64 near-band kernel.  Otherwise only pairs sharing a vertex are
 // skipped.
+//
+// The body works on one tile: targets I0 .. I0 + tcount - 1 (tcount <= kTile)
+// against sources s0 .. s1 - 1, writing partial-sum chunk `chunk`.  It is
+// called by the grid kernel (tile = blockIdx.x, chunk = blockIdx.y) and by
+// the persistent work-queue kernel of a batch (tiles and source ranges kept
+// inside one instance).
 template <typename R, int EC, bool GRAD, bool BAND>
-__global__ __launch_bounds__(kTile) void k_tpe_pairs(
-    const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB, const V4<R>* __restrict__ GT,
-    const int2* __restrict__ edges, const int4* __restrict__ cinfo, int nE, int src_per_chunk, R half_alpha,
-    R half_beta, R beta, double* __restrict__ part) {
+__device__ __forceinline__ void tpe_tile(const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB,
+                                         const V4<R>* __restrict__ GT, const int2* __restrict__ edges,
+                                         const int4* __restrict__ cinfo, int nE, int I0, int tcount, int s0, int s1,
+                                         int chunk, R half_alpha, R half_beta, R beta, double* __restrict__ part) {
   __shared__ V4<R> sA[kTile], sB[kTile], sT[kTile];
   __shared__ int2 sE[kTile];
   __shared__ int4 sC[BAND ? kTile : 1];
   const int tid = threadIdx.x;
-  const int I = blockIdx.x * kTile + tid;
-  const bool act = I < nE;
-  const int Ic = act ? I : nE - 1;
+  const int I = I0 + tid;
+  const bool act = tid < tcount;
+  const int Ic = act ? I : I0;
   const V4<R> a = GA[Ic], b = GB[Ic], t = GT[Ic];
   const int2 ei = act ? edges[Ic] : make_int2(-1, -2);
   int4 ci = make_int4(-1, 0, 0, 0);
@@ -82,8 +88,6 @@ __global__ __launch_bounds__(kTile) void k_tpe_pairs(
 #pragma unroll
   for (int k = 0; k < NS; ++k) acc[k] = 0.0;
 
-  const int s0 = blockIdx.y * src_per_chunk;
-  const int s1 = min(nE, s0 + src_per_chunk);
   for (int t0 = s0; t0 < s1; t0 += kTile) {
     __syncthreads();
     if (t0 + tid < s1) {
@@ -138,9 +142,45 @@ __global__ __launch_bounds__(kTile) void k_tpe_pairs(
     }
   }
   if (act) {
-    double* out = part + (size_t)blockIdx.y * NS * nE + I;
+    double* out = part + (size_t)chunk * NS * nE + I;
 #pragma unroll
     for (int k = 0; k < NS; ++k) out[(size_t)k * nE] = acc[k];
+  }
+}
+
+template <typename R, int EC, bool GRAD, bool BAND>
+__global__ __launch_bounds__(kTile) void k_tpe_pairs(
+    const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB, const V4<R>* __restrict__ GT,
+    const int2* __restrict__ edges, const int4* __restrict__ cinfo, int nE, int src_per_chunk, R half_alpha,
+    R half_beta, R beta, double* __restrict__ part) {
+  const int I0 = blockIdx.x * kTile;
+  const int s0 = blockIdx.y * src_per_chunk;
+  tpe_tile<R, EC, GRAD, BAND>(GA, GB, GT, edges, cinfo, nE, I0, min(kTile, nE - I0), s0,
+                              min(nE, s0 + src_per_chunk), blockIdx.y, half_alpha, half_beta, beta, part);
+}
+
+// Persistent work queue: items (t0, s0, s1, chunk << 16 | tcount), longest
+// first; every workgroup takes the next item from an atomic counter (zeroed
+// by k_zero_counter before the launch) until the list is exhausted.
+__device__ __forceinline__ int next_item(int* counter) {
+  __shared__ int it;
+  __syncthreads();
+  if (threadIdx.x == 0) it = atomicAdd(counter, 1);
+  __syncthreads();
+  return it;
+}
+
+__global__ void k_zero_counter(int* counter) { counter[0] = 0; }
+
+template <typename R, int EC, bool GRAD, bool BAND>
+__global__ __launch_bounds__(kTile) void k_tpe_items(
+    const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB, const V4<R>* __restrict__ GT,
+    const int2* __restrict__ edges, const int4* __restrict__ cinfo, int nE, const int4* __restrict__ items,
+    int n_items, int* __restrict__ counter, R half_alpha, R half_beta, R beta, double* __restrict__ part) {
+  for (int it = next_item(counter); it < n_items; it = next_item(counter)) {
+    const int4 w = items[it];
+    tpe_tile<R, EC, GRAD, BAND>(GA, GB, GT, edges, cinfo, nE, w.x, w.w & 0xffff, w.y, w.z, w.w >> 16, half_alpha,
+                                half_beta, beta, part);
   }
 }
 
@@ -199,16 +239,20 @@ __global__ void k_tpe_band(const V4<double>* __restrict__ GA, const V4<double>* 
 
 // Sum the chunks and turn the accumulators into per-edge energy and endpoint
 // partials: edge_out[I] = (E_I, dE/dg_i1 (3), dE/dg_i2 (3), -).
-__global__ void k_tpe_finalize(const double* __restrict__ part, int nchunk, int nE, int grad,
-                               const double* __restrict__ gd_a, const double* __restrict__ gd_t,
-                               double* __restrict__ edge_out) {
+// Chunks 0 .. n - 1 with n = nch_e[I] (batch) or nchunk, then the near-band
+// chunk `band_chunk` when it is >= 0.
+__global__ void k_tpe_finalize(const double* __restrict__ part, int nchunk, const int* __restrict__ nch_e,
+                               int band_chunk, int nE, int grad, const double* __restrict__ gd_a,
+                               const double* __restrict__ gd_t, double* __restrict__ edge_out) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nE) return;
   const int NS = grad ? kTpeSlots : 1;
+  const int nc = nch_e ? nch_e[I] : nchunk;
   double s[kTpeSlots];
   for (int k = 0; k < NS; ++k) {
     double v = 0.0;
-    for (int c = 0; c < nchunk; ++c) v += part[((size_t)c * NS + k) * nE + I];
+    for (int c = 0; c < nc; ++c) v += part[((size_t)c * NS + k) * nE + I];
+    if (band_chunk >= 0) v += part[((size_t)band_chunk * NS + k) * nE + I];
     s[k] = v;
   }
   const double l = gd_a[4 * I + 3];
@@ -302,23 +346,22 @@ __global__ void k_edge_rhs(const double* __restrict__ X, const int2* __restrict_
 }
 
 template <typename R, int EC>
-__global__ __launch_bounds__(kTile) void k_sob_pairs(
-    const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB, const V4<R>* __restrict__ GT,
-    const int2* __restrict__ edges, const V4<R>* __restrict__ RS, const V4<R>* __restrict__ RU,
-    int nE, int src_per_chunk, R half_expo, double* __restrict__ part) {
+__device__ __forceinline__ void sob_tile(const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB,
+                                         const V4<R>* __restrict__ GT, const int2* __restrict__ edges,
+                                         const V4<R>* __restrict__ RS, const V4<R>* __restrict__ RU, int nE, int I0,
+                                         int tcount, int s0, int s1, int chunk, R half_expo,
+                                         double* __restrict__ part) {
   __shared__ V4<R> sA[kTile], sB[kTile], sT[kTile], sS[kTile], sU[kTile];
   __shared__ int2 sE[kTile];
   const int tid = threadIdx.x;
-  const int I = blockIdx.x * kTile + tid;
-  const bool act = I < nE;
-  const int Ic = act ? I : nE - 1;
+  const int I = I0 + tid;
+  const bool act = tid < tcount;
+  const int Ic = act ? I : I0;
   const V4<R> a = GA[Ic], b = GB[Ic], t = GT[Ic];
   const int2 ei = act ? edges[Ic] : make_int2(-1, -2);
   double acc[kSobSlots];
 #pragma unroll
   for (int k = 0; k < kSobSlots; ++k) acc[k] = 0.0;
-  const int s0 = blockIdx.y * src_per_chunk;
-  const int s1 = min(nE, s0 + src_per_chunk);
   for (int t0 = s0; t0 < s1; t0 += kTile) {
     __syncthreads();
     if (t0 + tid < s1) {
@@ -378,23 +421,46 @@ __global__ __launch_bounds__(kTile) void k_sob_pairs(
     }
   }
   if (act) {
-    double* out = part + (size_t)blockIdx.y * kSobSlots * nE + I;
+    double* out = part + (size_t)chunk * kSobSlots * nE + I;
 #pragma unroll
     for (int k = 0; k < kSobSlots; ++k) out[(size_t)k * nE] = acc[k];
   }
 }
 
+template <typename R, int EC>
+__global__ __launch_bounds__(kTile) void k_sob_pairs(
+    const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB, const V4<R>* __restrict__ GT,
+    const int2* __restrict__ edges, const V4<R>* __restrict__ RS, const V4<R>* __restrict__ RU,
+    int nE, int src_per_chunk, R half_expo, double* __restrict__ part) {
+  const int I0 = blockIdx.x * kTile;
+  const int s0 = blockIdx.y * src_per_chunk;
+  sob_tile<R, EC>(GA, GB, GT, edges, RS, RU, nE, I0, min(kTile, nE - I0), s0, min(nE, s0 + src_per_chunk),
+                  blockIdx.y, half_expo, part);
+}
+
+template <typename R, int EC>
+__global__ __launch_bounds__(kTile) void k_sob_items(
+    const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB, const V4<R>* __restrict__ GT,
+    const int2* __restrict__ edges, const V4<R>* __restrict__ RS, const V4<R>* __restrict__ RU, int nE,
+    const int4* __restrict__ items, int n_items, int* __restrict__ counter, R half_expo, double* __restrict__ part) {
+  for (int it = next_item(counter); it < n_items; it = next_item(counter)) {
+    const int4 w = items[it];
+    sob_tile<R, EC>(GA, GB, GT, edges, RS, RU, nE, w.x, w.w & 0xffff, w.y, w.z, w.w >> 16, half_expo, part);
+  }
+}
+
 // Per edge: endpoint contributions of B u + B0 u (3 comps each) and the
 // diagonal pieces.  edge_out[I] = (y_i1 (3), y_i2 (3), dg_B, dg_B0).
-__global__ void k_sob_finalize(const double* __restrict__ part, int nchunk, int nE,
+__global__ void k_sob_finalize(const double* __restrict__ part, int nchunk, const int* __restrict__ nch_e, int nE,
                                const double* __restrict__ X, const int2* __restrict__ edges,
                                double* __restrict__ edge_out) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nE) return;
+  const int nc = nch_e ? nch_e[I] : nchunk;
   double s[kSobSlots];
   for (int k = 0; k < kSobSlots; ++k) {
     double v = 0.0;
-    for (int c = 0; c < nchunk; ++c) v += part[((size_t)c * kSobSlots + k) * nE + I];
+    for (int c = 0; c < nc; ++c) v += part[((size_t)c * kSobSlots + k) * nE + I];
     s[k] = v;
   }
   int2 e = edges[I];
@@ -659,6 +725,54 @@ __global__ void k_diag_rowsum(double* __restrict__ A, int nV) {
 }
 
 // ---------------------------------------------------------------------------
+// sphere-obstacle penalty (Sec. 7.1, surface potential; M a sphere)
+// ---------------------------------------------------------------------------
+// The surface integral of |x_M - y|^-p over a sphere of radius R and centre
+// c, at a point y with r = |y - c| > R, integrates in closed form over the
+// polar angle (u = r^2 + R^2 - 2 r R cos):
+//   Psi(r) = (pi R / r) [u^q / q] from (r-R)^2 to (r+R)^2,  q = 1 - p/2
+// (log for p = 2).  Per edge, with one midpoint sample: l_I Psi(|x_I - c|),
+// whose endpoint derivatives are -+T_I Psi + l_I Psi'(r) (x_I - c) / (2 r).
+// A midpoint on or inside the sphere makes the energy infinite.
+__global__ void k_obstacle(const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB,
+                           const V4<double>* __restrict__ GT, int nE, double cx, double cy, double cz, double R,
+                           double p, double w, int grad, double* __restrict__ edge_out) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nE) return;
+  const V4<double> a = GA[I], b = GB[I], t = GT[I];
+  const double dx = 0.5 * (a.x + b.x) - cx, dy = 0.5 * (a.y + b.y) - cy, dz = 0.5 * (a.z + b.z) - cz;
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const double l = a.w;
+  double* o = edge_out + 8 * (size_t)I;
+  if (!(r > R)) {
+    o[0] += INFINITY;
+    return;
+  }
+  const double hi = (r + R) * (r + R), lo = (r - R) * (r - R);
+  double F, dF;
+  if (p == 2.0) {
+    F = log(hi / lo);
+    dF = 2.0 / (r + R) - 2.0 / (r - R);
+  } else {
+    const double q = 1.0 - 0.5 * p;
+    const double hq = pow(hi, q), lq = pow(lo, q);
+    F = (hq - lq) / q;
+    dF = 2.0 * (r + R) * hq / hi - 2.0 * (r - R) * lq / lo;
+  }
+  const double psi = M_PI * R * F / r;
+  const double dpsi = M_PI * R * (dF / r - F / (r * r));
+  o[0] += w * l * psi;
+  if (!grad) return;
+  const double f = w * 0.5 * l * dpsi / r;
+  o[1] += -w * t.x * psi + f * dx;
+  o[2] += -w * t.y * psi + f * dy;
+  o[3] += -w * t.z * psi + f * dz;
+  o[4] += w * t.x * psi + f * dx;
+  o[5] += w * t.y * psi + f * dy;
+  o[6] += w * t.z * psi + f * dz;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
@@ -677,7 +791,25 @@ template <typename R, int EC, bool GRAD>
 static void run_tpe(const Curve& c, const EdgeGeom<R>& g, double alpha, double beta, hipStream_t s) {
   dim3 grid(cdiv(c.nE, kTile), c.nchunk);
   const bool timed = GRAD && c.timer && c.timer->on;
-  if (std::is_same<R, float>::value && c.chain) {
+  const bool band = std::is_same<R, float>::value && c.chain;
+  if (c.n_inst > 0) {
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, c.counter);
+    if (timed) c.timer->mark(c.timer->tpe, s);
+    if (band)
+      hipLaunchKernelGGL((k_tpe_items<R, EC, GRAD, true>), dim3(c.persist_blocks), dim3(kTile), 0, s, g.a, g.b, g.t,
+                         c.edges, c.cinfo, c.nE, c.items, c.n_items, c.counter, R(0.5 * alpha), R(0.5 * beta),
+                         R(beta), c.part);
+    else
+      hipLaunchKernelGGL((k_tpe_items<R, EC, GRAD, false>), dim3(c.persist_blocks), dim3(kTile), 0, s, g.a, g.b,
+                         g.t, c.edges, c.cinfo, c.nE, c.items, c.n_items, c.counter, R(0.5 * alpha), R(0.5 * beta),
+                         R(beta), c.part);
+    if (timed) c.timer->mark(c.timer->tpe, s);
+    if (band)
+      hipLaunchKernelGGL((k_tpe_band<EC, GRAD>), dim3(cdiv(c.nE, 64)), dim3(64), 0, s, c.gd.a, c.gd.b, c.gd.t,
+                         c.edges, c.cinfo, c.chain_edge, c.nE, 0.5 * alpha, 0.5 * beta, beta, c.nchunk, c.part);
+    return;
+  }
+  if (band) {
     if (timed) c.timer->mark(c.timer->tpe, s);
     hipLaunchKernelGGL((k_tpe_pairs<R, EC, GRAD, true>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, c.cinfo,
                        c.nE, c.src_per_chunk, R(0.5 * alpha), R(0.5 * beta), R(beta), c.part);
@@ -712,9 +844,15 @@ rc_status launch_tpe(const Curve& c, double alpha, double beta, rc_dtype prec, b
     else dispatch_tpe<double, false>(c, c.gd, alpha, beta, s);
   }
   RC_HIP(hipGetLastError());
-  const int nparts = c.nchunk + ((prec == RC_F32 && c.chain) ? 1 : 0);
-  hipLaunchKernelGGL(k_tpe_finalize, dim3(cdiv(c.nE, 256)), dim3(256), 0, s, c.part, nparts, c.nE,
-                     grad ? 1 : 0, (const double*)c.gd.a, (const double*)c.gd.t, c.edge_out);
+  const int band_chunk = (prec == RC_F32 && c.chain) ? c.nchunk : -1;
+  hipLaunchKernelGGL(k_tpe_finalize, dim3(cdiv(c.nE, 256)), dim3(256), 0, s, c.part, c.nchunk,
+                     (const int*)(c.n_inst > 0 ? c.nch_e : nullptr), band_chunk, c.nE, grad ? 1 : 0,
+                     (const double*)c.gd.a, (const double*)c.gd.t, c.edge_out);
+  if (c.obstacle.on) {
+    const Obstacle& o = c.obstacle;
+    hipLaunchKernelGGL(k_obstacle, dim3(cdiv(c.nE, 256)), dim3(256), 0, s, c.gd.a, c.gd.b, c.gd.t, c.nE, o.c[0],
+                       o.c[1], o.c[2], o.R, o.p, o.w, grad ? 1 : 0, c.edge_out);
+  }
   if (grad && dE)
     hipLaunchKernelGGL(k_gather_vertex, dim3(cdiv(c.nV, 256)), dim3(256), 0, s, c.edge_out, c.inc_off,
                        c.inc, c.nV, dE);
@@ -727,9 +865,14 @@ template <typename R, int EC>
 static void run_sob(const Curve& c, const EdgeGeom<R>& g, V4<R>* const* rhs, double half_expo, hipStream_t s) {
   dim3 grid(cdiv(c.nE, kTile), c.nchunk);
   const bool timed = std::is_same<R, float>::value && c.timer && c.timer->on;
+  if (c.n_inst > 0) hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, c.counter);
   if (timed) c.timer->mark(c.timer->sob, s);
-  hipLaunchKernelGGL((k_sob_pairs<R, EC>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, rhs[0], rhs[1],
-                     c.nE, c.src_per_chunk, R(half_expo), c.part);
+  if (c.n_inst > 0)
+    hipLaunchKernelGGL((k_sob_items<R, EC>), dim3(c.persist_blocks), dim3(kTile), 0, s, g.a, g.b, g.t, c.edges,
+                       rhs[0], rhs[1], c.nE, c.items, c.n_items, c.counter, R(half_expo), c.part);
+  else
+    hipLaunchKernelGGL((k_sob_pairs<R, EC>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, rhs[0], rhs[1],
+                       c.nE, c.src_per_chunk, R(half_expo), c.part);
   if (timed) c.timer->mark(c.timer->sob, s);
 }
 
@@ -757,7 +900,8 @@ rc_status launch_sobolev(const Curve& c, double alpha, double beta, rc_dtype pre
   }
   RC_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_edge_length<double>, g1, b1, 0, s, c.gd.a, c.nE, c.edge_out);
-  hipLaunchKernelGGL(k_sob_finalize, g1, b1, 0, s, c.part, c.nchunk, c.nE, X, c.edges, c.edge_out);
+  hipLaunchKernelGGL(k_sob_finalize, g1, b1, 0, s, c.part, c.nchunk,
+                     (const int*)(c.n_inst > 0 ? c.nch_e : nullptr), c.nE, X, c.edges, c.edge_out);
   hipLaunchKernelGGL(k_gather_sob, dim3(cdiv(c.nV, 256)), b1, 0, s, c.edge_out, c.inc_off, c.inc, c.nV, Y,
                      diag);
   RC_HIP(hipGetLastError());
@@ -807,11 +951,13 @@ rc_status finalize_midpoint(const Curve& c, int nparts, double* energy, double* 
 }
 
 // Per-edge (Wq, P0) of the operator kernel, stored in edge_out slots 0 and 1.
-__global__ void k_pick_wq_p0(const double* __restrict__ part, int nchunk, int nE, double* __restrict__ edge_out) {
+__global__ void k_pick_wq_p0(const double* __restrict__ part, int nchunk, const int* __restrict__ nch_e, int nE,
+                             double* __restrict__ edge_out) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nE) return;
   double wq = 0.0, p0 = 0.0;
-  for (int c = 0; c < nchunk; ++c) {
+  const int nc = nch_e ? nch_e[I] : nchunk;
+  for (int c = 0; c < nc; ++c) {
     wq += part[((size_t)c * kSobSlots + 0) * nE + I];
     p0 += part[((size_t)c * kSobSlots + 4) * nE + I];
   }
@@ -819,18 +965,26 @@ __global__ void k_pick_wq_p0(const double* __restrict__ part, int nchunk, int nE
   edge_out[8 * (size_t)I + 1] = p0;
 }
 
+// Zero right-hand sides by kernel (no memset nodes, so the call can be captured).
+template <typename R>
+__global__ void k_zero_rhs(V4<R>* __restrict__ a, V4<R>* __restrict__ b, int n) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= n) return;
+  a[I] = V4<R>{R(0), R(0), R(0), R(0)};
+  b[I] = V4<R>{R(0), R(0), R(0), R(0)};
+}
+
 rc_status launch_edge_sums(const Curve& c, double alpha, double beta, rc_dtype prec, hipStream_t s) {
   dim3 g1(cdiv(c.nE, 256)), b1(256);
   if (prec == RC_F32) {
-    RC_HIP(hipMemsetAsync(c.rhs_f[0], 0, sizeof(V4<float>) * c.nE, s));
-    RC_HIP(hipMemsetAsync(c.rhs_f[1], 0, sizeof(V4<float>) * c.nE, s));
+    hipLaunchKernelGGL(k_zero_rhs<float>, g1, b1, 0, s, c.rhs_f[0], c.rhs_f[1], c.nE);
     dispatch_sob<float>(c, c.gf, c.rhs_f, alpha, beta, s);
   } else {
-    RC_HIP(hipMemsetAsync(c.rhs_d[0], 0, sizeof(V4<double>) * c.nE, s));
-    RC_HIP(hipMemsetAsync(c.rhs_d[1], 0, sizeof(V4<double>) * c.nE, s));
+    hipLaunchKernelGGL(k_zero_rhs<double>, g1, b1, 0, s, c.rhs_d[0], c.rhs_d[1], c.nE);
     dispatch_sob<double>(c, c.gd, c.rhs_d, alpha, beta, s);
   }
-  hipLaunchKernelGGL(k_pick_wq_p0, g1, b1, 0, s, c.part, c.nchunk, c.nE, c.edge_out);
+  hipLaunchKernelGGL(k_pick_wq_p0, g1, b1, 0, s, c.part, c.nchunk, (const int*)(c.n_inst > 0 ? c.nch_e : nullptr),
+                     c.nE, c.edge_out);
   RC_HIP(hipGetLastError());
   return RC_OK;
 }

@@ -127,4 +127,70 @@ __device__ __forceinline__ void tpe_vertex_pair(
   }
 }
 
+// ---------------------------------------------------------------------------
+// one entry of the assembled operator A = B + B0 (Sec. 4.2.2-4.2.3)
+// ---------------------------------------------------------------------------
+// Entry (v, w), v != w, of the dense matrix the increment tables assemble: the
+// sum over disjoint edges I at v and J at w of
+//     -1/2 s_I(v) s_J(w) rho_IJ <T_I, T_J>  -  l_I l_J rho0_IJ / 16
+// (rho_IJ: the sum over the four vertex pairs of |d|^-(2 sigma + 1); rho0_IJ
+// the same weighted by the low-order kernel k_{2,4} with T_I and with T_J),
+// plus, when v and w are the two ends of an edge K, -Wq_K / (2 l_K) + l_K P0_K / 16,
+// with s(i1) = -1, s(i2) = +1 and Wq, P0 the per-edge sums of the operator
+// kernel (edge_out slots 0 and 1).
+// Off-diagonal entry A_vw (v != w) evaluated in precision R from the FP64
+// geometry: coordinate differences are taken in FP64 and then rounded, so an
+// FP32 entry carries a few ulps of error even for vertices close together
+// (differences of rounded coordinates would lose bits in proportion to
+// |x| / |x_v - x_w|).
+template <typename R, int EC>
+__device__ __forceinline__ R sobolev_entry(int v, int w, const V4<double>* __restrict__ GA,
+                                        const V4<double>* __restrict__ GB, const V4<double>* __restrict__ GT,
+                                        const int2* __restrict__ edges, const int* __restrict__ inc_off,
+                                        const int* __restrict__ inc, const double* __restrict__ edge_out,
+                                        R half_expo) {
+  R acc = R(0);
+  const int kw0 = inc_off[w], kw1 = inc_off[w + 1];
+  for (int kv = inc_off[v]; kv < inc_off[v + 1]; ++kv) {
+    const int I = inc[kv] >> 1;
+    const R sv = (inc[kv] & 1) ? R(1) : R(-1);
+    const int2 ei = edges[I];
+    const V4<double> ia = GA[I], ib = GB[I], tid = GT[I];
+    const R tix = (R)tid.x, tiy = (R)tid.y, tiz = (R)tid.z, li = (R)ia.w;
+    for (int kw = kw0; kw < kw1; ++kw) {
+      const int J = inc[kw] >> 1;
+      if (I == J) {
+        const double* o = edge_out + 8 * (size_t)I;  // (Wq, P0) in slots 0, 1
+        const double l = ia.w;
+        acc += (R)(-o[0] / (2.0 * l) + l * o[1] / 16.0);
+        continue;
+      }
+      const int2 ej = edges[J];
+      if (ei.x == ej.x || ei.x == ej.y || ei.y == ej.x || ei.y == ej.y) continue;
+      const R sw = (inc[kw] & 1) ? R(1) : R(-1);
+      const V4<double> ja = GA[J], jb = GB[J], tjd = GT[J];
+      const R tjx = (R)tjd.x, tjy = (R)tjd.y, tjz = (R)tjd.z;
+      R rho = R(0), rho0 = R(0);
+      const V4<double>* P[2] = {&ia, &ib};
+      const V4<double>* Q[2] = {&ja, &jb};
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const R dx = (R)(P[x]->x - Q[y]->x), dy = (R)(P[x]->y - Q[y]->y), dz = (R)(P[x]->z - Q[y]->z);
+          const R r2 = dx * dx + dy * dy + dz * dz;
+          const R rs = f_rsq<R>(r2), ri = rs * rs;
+          const R p = pow_sigma<EC, R>(r2, rs, ri, half_expo);
+          const R cI = cross_norm2<R>(tix, tiy, tiz, dx, dy, dz);
+          const R cJ = cross_norm2<R>(tjx, tjy, tjz, dx, dy, dz);
+          rho += p;
+          rho0 += p * (cI + cJ) * ri * ri;
+        }
+      const R tt = tix * tjx + tiy * tjy + tiz * tjz;
+      acc += R(-0.5) * sv * sw * rho * tt - R(0.0625) * li * (R)ja.w * rho0;
+    }
+  }
+  return acc;
+}
+
 }  // namespace rc

@@ -100,6 +100,15 @@ struct KernelTimer {
   }
 };
 
+// Sphere-obstacle penalty (Sec. 7.1, surface potential with M a sphere):
+// E_M = w sum_I l_I Psi(|x_I - c|), Psi the closed-form shell potential of
+// exponent p = beta - alpha.
+struct Obstacle {
+  bool on = false;
+  double c[3] = {0, 0, 0};
+  double R = 0, p = 0, w = 0;
+};
+
 // A curve network on the device (the finest level, or a multigrid level).
 struct Curve {
   int nV = 0, nE = 0;
@@ -122,12 +131,29 @@ struct Curve {
   KernelTimer* timer = nullptr;    // set on the finest level when profiling is on
 
   int nchunk = 1, src_per_chunk = 0;
+  int part_chunks = 0;             // chunks part has room for (the near band uses chunk nchunk)
   double* part = nullptr;          // pair-kernel partials, sized for the largest slot count
   double* edge_out = nullptr;      // per-edge finalised values [nE][8]
   double* red = nullptr;           // reduction scratch
   int red_blocks = 0;
 
+  // Batch of independent instances (n_inst > 0): the vertices and edges of
+  // instance i are contiguous, and the pair kernels sum over pairs of one
+  // instance only, as work items (target tile, source range) of a persistent
+  // launch.  nchunk is then the largest chunk count of an instance and nch_e
+  // gives every edge its instance's count.
+  int n_inst = 0;
+  std::vector<int> h_inst_voff, h_inst_eoff;
+  int *inst_voff = nullptr, *inst_eoff = nullptr, *inst_of_edge = nullptr, *inst_of_vertex = nullptr;
+  int4* items = nullptr;           // (t0, s0, s1, chunk << 16 | tcount), longest first
+  int n_items = 0, item_src = 0, persist_blocks = 0, blocks_per_cu = 0;
+  int* nch_e = nullptr;
+  int* counter = nullptr;
+  Obstacle obstacle;               // applied by launch_tpe when on
+
   rc_status init(int nV_, int nE_, const int* edges_h);
+  rc_status set_instances(int n_inst_, const int* voff_h);
+  rc_status build_items(int src_chunk, int blocks_per_cu_);
   void release();
 };
 

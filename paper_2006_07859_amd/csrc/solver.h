@@ -55,6 +55,35 @@ struct MGLevelState {
   double lmax = 0.0;
 };
 
+// Batch solver state: the union of independent instances, each with its
+// own barycenter and per-loop length constraints, PCG scalars and line search.
+constexpr int kBatchScal = 16;  // per-instance PCG scalars
+constexpr int kBatchLs = 16;    // per-instance line-search values
+struct Batch {
+  bool ready = false;
+  int n_inst = 0, nq = 0;
+  std::vector<int> h_chain_voff, h_inst_qoff, h_chain_eoff;
+  int *chain_vert = nullptr, *chain_voff = nullptr, *chain_of_vertex = nullptr, *chain_inst = nullptr;
+  int *inst_qoff = nullptr, *chain_eoff = nullptr, *chain_edges = nullptr;
+  long long* blk_off = nullptr;   // offsets of the loop blocks in Minv
+  size_t blk_total = 0;
+  int max_chain = 0;
+  double *Minv = nullptr, *gj_col = nullptr;
+  double *x0 = nullptr, *L0 = nullptr;
+  double *Jv = nullptr, *Lv = nullptr, *qsum = nullptr, *Sinv = nullptr, *cq = nullptr, *yb = nullptr, *yq = nullptr;
+  double *dvec = nullptr;
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *b = nullptr, *t = nullptr;
+  double *sc = nullptr, *ls = nullptr, *energy = nullptr, *stats = nullptr;
+  double *trial = nullptr, *ghat = nullptr, *dE = nullptr, *g = nullptr, *inc = nullptr;
+  double *phiq = nullptr, *phib = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool captured = false;
+  rc_batch_opts cap_opts{};
+  const double* cap_gamma = nullptr;
+};
+
 }  // namespace rc
 
 struct rc_ctx {
@@ -83,6 +112,7 @@ struct rc_ctx {
   rc::LowpOp lowp;
   int lowp_levels = 0, lowp_fmt = 0, lowp_band = 0, lowp_outer = 0;
   int last_sweeps = 0;  // FP64 true-residual evaluations of the last PCG solve
+  rc::Batch batch;      // batch contexts only
 };
 
 namespace rc {
@@ -112,5 +142,13 @@ struct LsResult {
 };
 rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, const double* g, const rc_ls_opts& ls,
                       const rc_solve_opts& so, LsResult* out);
+
+// batch.hip
+rc_status batch_alloc(rc_ctx* c);
+void batch_free(rc_ctx* c);
+rc_status batch_edge_sums(rc_ctx* c, int slot, double* out);
+rc_status batch_set_constraints(rc_ctx* c, const double* gamma_ref);
+rc_status batch_gradient(rc_ctx* c, const double* gamma, const double* dE, double* g, const rc_batch_opts& o);
+rc_status batch_step(rc_ctx* c, double* gamma, const rc_batch_opts& o, double* stats_h);
 
 }  // namespace rc
