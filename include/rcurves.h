@@ -308,6 +308,17 @@ rc_status rc_batch_energies(rc_ctx* ctx, const double* gamma, double* energies, 
  * unit (1 .. 32).  Synchronises the stream. */
 rc_status rc_batch_tiling(rc_ctx* ctx, int32_t src_chunk, int32_t blocks_per_cu);
 
+/* Chooses the work-item shape of the batch pair kernels by timing candidate
+ * source-range lengths (512 .. 4096) and persistent workgroups per compute
+ * unit (4, 8, 16) on one energy + differential and one operator application
+ * at gamma (device double[nV][3]), and keeps the fastest.  cache_path (host
+ * string or NULL): a JSON file of earlier choices keyed by GPU architecture,
+ * kernel and size class; a hit skips the timing, a new result is added.
+ * Outputs (host): the chosen src_chunk, blocks_per_cu and the timed ms per
+ * (energy + differential + operator).  Synchronises the stream. */
+rc_status rc_batch_autotune(rc_ctx* ctx, const double* gamma, const char* cache_path, int32_t* src_chunk,
+                            int32_t* blocks_per_cu, double* ms);
+
 /* Defaults of rc_batch_opts. */
 void rc_default_batch_opts(rc_batch_opts* opts);
 

@@ -33,7 +33,7 @@ EXPORTED = [
     "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_bh_last_work", "rc_midpoint_differential",
     "rc_profile_enable", "rc_profile_read", "rc_lowp_assemble", "rc_lowp_apply", "rc_set_obstacle",
     "rc_create_batch", "rc_batch_size", "rc_batch_energies", "rc_batch_tiling", "rc_default_batch_opts",
-    "rc_batch_set_constraints", "rc_batch_gradient", "rc_batch_step", "rc_batch_pcg_state",
+    "rc_batch_set_constraints", "rc_batch_gradient", "rc_batch_step", "rc_batch_pcg_state", "rc_batch_autotune",
 ]
 
 
@@ -121,6 +121,7 @@ def load():
         "rc_batch_gradient": (I32, [P, P, P, P, P]),
         "rc_batch_step": (I32, [P, P, P, P]),
         "rc_batch_pcg_state": (I32, [P, P, P]),
+        "rc_batch_autotune": (I32, [P, P, C.c_char_p, C.POINTER(I32), C.POINTER(I32), C.POINTER(D)]),
         "rc_lowp_apply": (I32, [P, P, P, I32]),
     }
     for name, (res, args) in sig.items():
@@ -354,6 +355,12 @@ class Batch(Context):
         _check(load().rc_batch_step(self.h, self._v(gamma, "gamma"), C.byref(o),
                                     None if out is None else out.ctypes.data_as(C.c_void_p)))
         return out
+
+    def rc_batch_autotune(self, gamma, cache_path=None):
+        a, b, ms = C.c_int32(), C.c_int32(), C.c_double()
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(load().rc_batch_autotune(self.h, self._v(gamma, "gamma"), path, C.byref(a), C.byref(b), C.byref(ms)))
+        return {"src_chunk": a.value, "blocks_per_cu": b.value, "ms": ms.value}
 
     def rc_batch_pcg_state(self):
         it, res = np.zeros(self.n_inst), np.zeros(self.n_inst)

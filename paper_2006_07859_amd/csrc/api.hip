@@ -550,7 +550,25 @@ extern "C" rc_status rc_batch_tiling(rc_ctx* c, int32_t src_chunk, int32_t block
     return RC_ERR_ARG;
   }
   RC_HIP(hipStreamSynchronize(c->stream));
+  batch_invalidate_graph(c);
   return c->curve.build_items(src_chunk, blocks_per_cu);
+}
+
+extern "C" rc_status rc_batch_autotune(rc_ctx* c, const double* gamma, const char* cache_path, int32_t* src_chunk,
+                                       int32_t* blocks_per_cu, double* ms) {
+  RC_TRY(check_ctx(c));
+  if (c->curve.n_inst == 0) {
+    set_error("rc_batch_autotune: not a batch context");
+    return RC_ERR_ARG;
+  }
+  RC_TRY(check_ptrs({gamma, src_chunk, blocks_per_cu, ms}));
+  int a = 0, b = 0;
+  double t = 0.0;
+  RC_TRY(batch_autotune(c, gamma, cache_path, &a, &b, &t));
+  *src_chunk = a;
+  *blocks_per_cu = b;
+  *ms = t;
+  return RC_OK;
 }
 
 extern "C" void rc_default_batch_opts(rc_batch_opts* o) {

@@ -26,7 +26,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
 
 #include "k_linalg.h"
 #include "pair_math.h"
@@ -383,49 +387,130 @@ __global__ void k_b_blocks(const V4<double>* __restrict__ GA, const V4<double>* 
   Minv[k] = val;
 }
 
-// In-place Gauss-Jordan inverse of every loop block (symmetric positive
-// definite: no pivoting), one workgroup per loop; col is scratch of the
-// loop's size.  For step k: scale row k by 1/M_kk (with M_kk replaced by 1),
-// then every other row i loses M_ik times row k (with M_ik replaced by 0).
-__global__ __launch_bounds__(256) void k_b_gauss_jordan(const int* __restrict__ chain_voff,
-                                                        const long long* __restrict__ blk_off,
-                                                        double* __restrict__ Minv, double* __restrict__ colbuf) {
-  const int q = blockIdx.x;
+// Inverse of every loop block by blocked Gauss-Jordan (symmetric positive
+// definite: no pivoting), in place, with 32 x 32 tiles.  Tile step k:
+//   A_kk <- A_kk^-1,  A_kj <- A_kk^-1 A_kj (j != k),
+//   A_ij <- A_ij - A_ik A_kj,  A_ik <- -A_ik A_kk^-1 (i != k),
+// with the old column panel A_ik saved first.  k_gj_panel does the diagonal
+// tile, the saved column and the row panel of every block that has tile k
+// (one workgroup per block); k_gj_update every other tile of those blocks
+// (one workgroup per tile), so a step runs on the whole GPU.
+constexpr int kGT = 32;
+
+__global__ __launch_bounds__(256) void k_gj_panel(int k, const int* __restrict__ list,
+                                                  const int* __restrict__ chain_voff,
+                                                  const long long* __restrict__ blk_off, double* __restrict__ Minv,
+                                                  double* __restrict__ S) {
+  __shared__ double D[kGT][kGT + 1];
+  __shared__ double f[kGT];
+  const int q = list[blockIdx.x];
   const int m = chain_voff[q + 1] - chain_voff[q];
   double* M = Minv + blk_off[q];
-  double* f = colbuf + chain_voff[q];
-  for (int k = 0; k < m; ++k) {
-    const double piv = M[(size_t)k * m + k];
+  double* Sq = S + (size_t)chain_voff[q] * kGT;
+  const int r0 = k * kGT, kk = min(kGT, m - r0);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kGT * kGT; e += 256) {
+    const int r = e / kGT, c = e % kGT;
+    D[r][c] = (r < kk && c < kk) ? M[(size_t)(r0 + r) * m + r0 + c] : (r == c ? 1.0 : 0.0);
+  }
+  // the old column panel, before row k changes
+  for (int e = tid; e < m * kGT; e += 256) {
+    const int i = e / kGT, c = e % kGT;
+    Sq[e] = c < kk ? M[(size_t)i * m + r0 + c] : 0.0;
+  }
+  __syncthreads();
+  // scalar Gauss-Jordan of the diagonal tile in LDS
+  for (int p = 0; p < kGT; ++p) {
+    const double ip = 1.0 / D[p][p];
     __syncthreads();
-    const double ip = 1.0 / piv;
-    for (int j = threadIdx.x; j < m; j += 256) {
-      const double val = (j == k) ? 1.0 : M[(size_t)k * m + j];
-      M[(size_t)k * m + j] = val * ip;
+    if (tid < kGT) {
+      f[tid] = tid == p ? 0.0 : D[tid][p];
+      D[p][tid] = (tid == p ? 1.0 : D[p][tid]) * ip;
     }
-    for (int i = threadIdx.x; i < m; i += 256) f[i] = (i == k) ? 0.0 : M[(size_t)i * m + k];
     __syncthreads();
-    for (int i = 0; i < m; ++i) {
-      const double fi = f[i];
-      if (fi == 0.0) continue;
-      for (int j = threadIdx.x; j < m; j += 256) {
-        const double rk = M[(size_t)k * m + j];
-        M[(size_t)i * m + j] = (j == k) ? -fi * rk : M[(size_t)i * m + j] - fi * rk;
-      }
+    for (int e = tid; e < kGT * kGT; e += 256) {
+      const int r = e / kGT, c = e % kGT;
+      if (r == p) continue;
+      D[r][c] = (c == p) ? -f[r] * D[p][p] : D[r][c] - f[r] * D[p][c];
     }
     __syncthreads();
   }
+  // row panel: A_kj <- Dinv A_kj for the columns outside tile k
+  for (int c = tid; c < m; c += 256) {
+    if (c >= r0 && c < r0 + kk) continue;
+    double col[kGT];
+#pragma unroll
+    for (int s2 = 0; s2 < kGT; ++s2) col[s2] = s2 < kk ? M[(size_t)(r0 + s2) * m + c] : 0.0;
+    for (int r = 0; r < kk; ++r) {
+      double a = 0.0;
+#pragma unroll
+      for (int s2 = 0; s2 < kGT; ++s2) a += D[r][s2] * col[s2];
+      M[(size_t)(r0 + r) * m + c] = a;
+    }
+  }
+  for (int e = tid; e < kk * kk; e += 256) {
+    const int r = e / kk, c = e % kk;
+    M[(size_t)(r0 + r) * m + r0 + c] = D[r][c];
+  }
 }
 
-// z_v = sum_{w in loop(v)} Minv[v][w] r_w, one workgroup per loop, a wave per row.
-__global__ __launch_bounds__(256) void k_b_prec(const int* __restrict__ chain_vert, const int* __restrict__ chain_voff,
+// Flat workgroup index -> (block, tile i, tile j) through the step's prefix
+// of tile counts (binary search).
+__global__ __launch_bounds__(256) void k_gj_update(int k, const int* __restrict__ list,
+                                                   const int* __restrict__ pre, int nact,
+                                                   const int* __restrict__ chain_voff,
+                                                   const long long* __restrict__ blk_off, double* __restrict__ Minv,
+                                                   const double* __restrict__ S) {
+  __shared__ double Sa[kGT][kGT + 1], Bt[kGT][kGT + 1];
+  const int w = blockIdx.x;
+  int lo = 0, hi = nact - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (pre[mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  const int q = list[lo];
+  const int m = chain_voff[q + 1] - chain_voff[q];
+  const int nb = (m + kGT - 1) / kGT;
+  const int t = w - pre[lo];
+  const int ti = t / nb, tj = t % nb;
+  if (ti == k) return;
+  double* M = Minv + blk_off[q];
+  const double* Sq = S + (size_t)chain_voff[q] * kGT;
+  const int r0 = k * kGT, kk = min(kGT, m - r0);
+  const int i0 = ti * kGT, ki = min(kGT, m - i0);
+  const int j0 = tj * kGT, kj = min(kGT, m - j0);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kGT * kGT; e += 256) {
+    const int r = e / kGT, c = e % kGT;
+    Sa[r][c] = r < ki ? Sq[(size_t)(i0 + r) * kGT + c] : 0.0;
+    Bt[r][c] = (r < kk && c < kj) ? M[(size_t)(r0 + r) * m + j0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < kGT * kGT; e += 256) {
+    const int r = e / kGT, c = e % kGT;
+    if (r >= ki || c >= kj) continue;
+    double a = 0.0;
+#pragma unroll 8
+    for (int s2 = 0; s2 < kGT; ++s2) a += Sa[r][s2] * Bt[s2][c];
+    const size_t idx = (size_t)(i0 + r) * m + j0 + c;
+    M[idx] = (tj == k) ? -a : M[idx] - a;
+  }
+}
+
+// z_v = sum_{w in loop(v)} Minv[v][w] r_w: each workgroup takes 16 rows of one
+// loop (work items (loop, first row)), a wave per row, lanes along the row.
+__global__ __launch_bounds__(256) void k_b_prec(const int2* __restrict__ prec_items,
+                                                const int* __restrict__ chain_vert, const int* __restrict__ chain_voff,
                                                 const long long* __restrict__ blk_off, const double* __restrict__ Minv,
                                                 const double* __restrict__ r, double* __restrict__ z) {
-  const int q = blockIdx.x;
+  const int2 it = prec_items[blockIdx.x];
+  const int q = it.x;
   const int m = chain_voff[q + 1] - chain_voff[q];
   const int* vs = chain_vert + chain_voff[q];
   const double* M = Minv + blk_off[q];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  for (int a = wave; a < m; a += 4) {
+  for (int a = it.y + wave; a < min(m, it.y + 16); a += 4) {
     double s0 = 0, s1 = 0, s2 = 0;
     for (int b = lane; b < m; b += 64) {
       const double mv = M[(size_t)a * m + b];
@@ -461,13 +546,15 @@ __global__ void k_b_copy(const double* __restrict__ x, double* __restrict__ y, i
   if (k < n) y[k] = x[k];
 }
 
-// PCG start: bb = <r, r>, active = (bb > 0), its = 0.
-__global__ void k_b_pcg_start(double* __restrict__ sc, int n_inst) {
+// PCG start: bb = <r, r>, active = (bb > 0) (and the instance still
+// searching for a step when ls is given), its = 0.
+__global__ void k_b_pcg_start(double* __restrict__ sc, int n_inst, const double* __restrict__ ls) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_inst) return;
   double* S = sc + (size_t)i * kBatchScal;
   S[S_BB] = S[S_RR];
-  S[S_ACT] = S[S_BB] > 0.0 ? 1.0 : 0.0;
+  const bool on = !ls || ls[(size_t)i * kBatchLs + L_DONE] == 0.0;
+  S[S_ACT] = (S[S_BB] > 0.0 && on) ? 1.0 : 0.0;
   S[S_ITS] = 0.0;
   S[S_RES] = S[S_BB] > 0.0 ? 1.0 : 0.0;
 }
@@ -522,6 +609,17 @@ __global__ void k_b_pupd(const int* __restrict__ inst_of_vertex, const double* _
   const double* S = sc + (size_t)inst_of_vertex[k / 3] * kBatchScal;
   if (!(S[S_ACT] > 0.0)) return;
   p[k] = z[k] + S[S_BETA] * p[k];
+}
+
+// Work masks of the persistent pair kernels: instances still iterating (PCG)
+// or still searching for a step (line search).
+__global__ void k_b_mask_pcg(const double* __restrict__ sc, int n_inst, int* __restrict__ mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_inst) mask[i] = sc[(size_t)i * kBatchScal + S_ACT] > 0.0 ? 1 : 0;
+}
+__global__ void k_b_mask_ls(const double* __restrict__ ls, int n_inst, int* __restrict__ mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_inst) mask[i] = ls[(size_t)i * kBatchLs + L_DONE] == 0.0 ? 1 : 0;
 }
 
 __global__ void k_b_active_count(const double* __restrict__ sc, int n_inst, double* __restrict__ out) {
@@ -705,7 +803,46 @@ rc_status batch_alloc(rc_ctx* c) {
   RC_HIP(hipMemcpy(B.blk_off, boff.data(), sizeof(long long) * (B.nq + 1), hipMemcpyHostToDevice));
   const size_t n3 = 3 * (size_t)nV;
   RC_TRY(balloc(&B.Minv, B.blk_total));
-  RC_TRY(balloc(&B.gj_col, nV));
+  RC_TRY(balloc(&B.gj_col, (size_t)kGT * nV));
+  // tile steps of the blocked inversion: the blocks that have tile k, with
+  // prefix sums of their tile counts; work items of the block products
+  {
+    std::vector<int> nbq(B.nq);
+    int max_nb = 0;
+    for (int q = 0; q < B.nq; ++q) {
+      nbq[q] = (cvoff[q + 1] - cvoff[q] + kGT - 1) / kGT;
+      max_nb = std::max(max_nb, nbq[q]);
+    }
+    std::vector<int> list, pre;
+    B.h_gj_step_off.assign(1, 0);
+    B.h_gj_tiles.clear();
+    for (int k = 0; k < max_nb; ++k) {
+      long long acc = 0;
+      for (int q = 0; q < B.nq; ++q)
+        if (nbq[q] > k) {
+          list.push_back(q);
+          pre.push_back((int)acc);
+          acc += (long long)nbq[q] * nbq[q];
+        }
+      if (acc >= (1LL << 31)) {
+        set_error("batch loop blocks too large");
+        return RC_ERR_UNSUPPORTED;
+      }
+      B.h_gj_tiles.push_back((int)acc);
+      B.h_gj_step_off.push_back((int)list.size());
+    }
+    B.gj_steps = max_nb;
+    RC_TRY(balloc(&B.gj_list, list.size()));
+    RC_TRY(balloc(&B.gj_pre, pre.size()));
+    RC_HIP(hipMemcpy(B.gj_list, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice));
+    RC_HIP(hipMemcpy(B.gj_pre, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice));
+    std::vector<int2> pit;
+    for (int q = 0; q < B.nq; ++q)
+      for (int r0 = 0; r0 < cvoff[q + 1] - cvoff[q]; r0 += 16) pit.push_back(make_int2(q, r0));
+    B.n_prec = (int)pit.size();
+    RC_TRY(balloc(&B.prec_items, pit.size()));
+    RC_HIP(hipMemcpy(B.prec_items, pit.data(), sizeof(int2) * pit.size(), hipMemcpyHostToDevice));
+  }
   RC_TRY(balloc(&B.x0, 3 * (size_t)B.n_inst));
   RC_TRY(balloc(&B.L0, B.nq));
   RC_TRY(balloc(&B.Jv, 9 * (size_t)nV));
@@ -723,6 +860,7 @@ rc_status batch_alloc(rc_ctx* c) {
   RC_TRY(balloc(&B.energy, B.n_inst));
   RC_TRY(balloc(&B.stats, 8 * (size_t)B.n_inst + 8));
   RC_TRY(balloc(&B.phiq, B.nq));
+  RC_TRY(balloc(&B.mask, B.n_inst));
   RC_TRY(balloc(&B.phib, 3 * (size_t)B.n_inst));
   RC_HIP(hipMemset(B.ls, 0, sizeof(double) * kBatchLs * B.n_inst));
   RC_HIP(hipMemset(B.sc, 0, sizeof(double) * kBatchScal * B.n_inst));
@@ -737,7 +875,7 @@ void batch_free(rc_ctx* c) {
   void* ps[] = {B.chain_vert, B.chain_voff, B.chain_of_vertex, B.chain_inst, B.inst_qoff, B.chain_eoff,
                 B.chain_edges, B.blk_off, B.Minv, B.gj_col, B.x0, B.L0, B.Jv, B.Lv, B.qsum, B.Sinv, B.cq,
                 B.yb, B.yq, B.dvec, B.x, B.r, B.z, B.p, B.q, B.b, B.t, B.trial, B.ghat, B.dE, B.g, B.inc,
-                B.sc, B.ls, B.energy, B.stats, B.phiq, B.phib};
+                B.sc, B.ls, B.energy, B.stats, B.phiq, B.phib, B.mask, B.gj_list, B.gj_pre, B.prec_items};
   for (void* p : ps)
     if (p) hipFree(p);
   B = Batch();
@@ -806,7 +944,13 @@ static rc_status b_prepare(rc_ctx* c) {
     default: RC_BLK(kGeneral); break;
   }
 #undef RC_BLK
-  hipLaunchKernelGGL(k_b_gauss_jordan, dim3(B.nq), dim3(256), 0, s, B.chain_voff, B.blk_off, B.Minv, B.gj_col);
+  for (int k = 0; k < B.gj_steps; ++k) {
+    const int off = B.h_gj_step_off[k], nact = B.h_gj_step_off[k + 1] - off;
+    hipLaunchKernelGGL(k_gj_panel, dim3(nact), dim3(256), 0, s, k, B.gj_list + off, B.chain_voff, B.blk_off, B.Minv,
+                       B.gj_col);
+    hipLaunchKernelGGL(k_gj_update, dim3(B.h_gj_tiles[k]), dim3(256), 0, s, k, B.gj_list + off, B.gj_pre + off, nact,
+                       B.chain_voff, B.blk_off, B.Minv, (const double*)B.gj_col);
+  }
   RC_HIP(hipGetLastError());
   return RC_OK;
 }
@@ -814,8 +958,8 @@ static rc_status b_prepare(rc_ctx* c) {
 // z = P M^-1 P r (r already in range P).
 static void b_precondition(rc_ctx* c, const double* r, double* z) {
   Batch& B = c->batch;
-  hipLaunchKernelGGL(k_b_prec, dim3(B.nq), dim3(256), 0, c->stream, B.chain_vert, B.chain_voff, B.blk_off, B.Minv, r,
-                     z);
+  hipLaunchKernelGGL(k_b_prec, dim3(B.n_prec), dim3(256), 0, c->stream, B.prec_items, B.chain_vert, B.chain_voff,
+                     B.blk_off, B.Minv, r, z);
   b_project(c, z, z);
 }
 
@@ -829,7 +973,8 @@ static rc_status b_operator(rc_ctx* c, const double* p, double* q) {
 // Projected PCG on every instance: x = (P Abar P)^+ P rhs, to the relative
 // residual tol or max_it iterations.  check_every > 0 (never while
 // capturing): stop once no instance is active, checked on the host.
-static rc_status b_pcg(rc_ctx* c, const double* rhs, double* x, double tol, int max_it, int check_every) {
+static rc_status b_pcg(rc_ctx* c, const double* rhs, double* x, double tol, int max_it, int check_every,
+                       const double* ls_mask) {
   Batch& B = c->batch;
   hipStream_t s = c->stream;
   const int nV = c->nV, n3 = 3 * nV;
@@ -839,12 +984,17 @@ static rc_status b_pcg(rc_ctx* c, const double* rhs, double* x, double tol, int 
   b_project(c, rhs, B.r);
   hipLaunchKernelGGL(k_b_fill, gv, bv, 0, s, x, (size_t)n3, 0.0);
   hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.r, B.r, vo, B.sc, kBatchScal, (int)S_RR);
-  hipLaunchKernelGGL(k_b_pcg_start, gi, bi, 0, s, B.sc, B.n_inst);
+  hipLaunchKernelGGL(k_b_pcg_start, gi, bi, 0, s, B.sc, B.n_inst, ls_mask);
   b_precondition(c, B.r, B.z);
   hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.r, B.z, vo, B.sc, kBatchScal, (int)S_RZ);
   hipLaunchKernelGGL(k_b_copy, gv, bv, 0, s, B.z, B.p, n3);
   for (int it = 0; it < max_it; ++it) {
-    RC_TRY(b_operator(c, B.p, B.q));
+    // only instances still iterating pay for the operator
+    hipLaunchKernelGGL(k_b_mask_pcg, gi, bi, 0, s, B.sc, B.n_inst, B.mask);
+    c->curve.inst_mask = B.mask;
+    const rc_status so = b_operator(c, B.p, B.q);
+    c->curve.inst_mask = nullptr;
+    RC_TRY(so);
     hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.p, B.q, vo, B.sc, kBatchScal, (int)S_PQ);
     hipLaunchKernelGGL(k_b_pcg_alpha, gi, bi, 0, s, B.sc, B.n_inst);
     hipLaunchKernelGGL(k_b_xr, gv, bv, 0, s, iv, B.sc, nV, B.p, B.q, x, B.r);
@@ -872,7 +1022,7 @@ rc_status batch_gradient(rc_ctx* c, const double* gamma, const double* dE, doubl
   }
   RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));
   RC_TRY(b_prepare(c));
-  return b_pcg(c, dE, g, o.tol, o.max_iter, o.check_every);
+  return b_pcg(c, dE, g, o.tol, o.max_iter, o.check_every, nullptr);
 }
 
 // The whole step on the context stream, without host synchronisation when
@@ -893,7 +1043,7 @@ static rc_status b_step(rc_ctx* c, double* gamma, const rc_batch_opts& o, int ch
   hipLaunchKernelGGL(k_b_fill, dim3(cdiv(kBatchLs * B.n_inst, 256)), bv, 0, s, B.ls, (size_t)kBatchLs * B.n_inst, 0.0);
   // constraints and preconditioner at gamma, projected gradient
   RC_TRY(b_prepare(c));
-  RC_TRY(b_pcg(c, B.dE, B.g, o.tol, o.max_iter, check_every));
+  RC_TRY(b_pcg(c, B.dE, B.g, o.tol, o.max_iter, check_every, nullptr));
   // per-instance line search
   hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.g, B.g, vo, B.ls, kBatchLs, (int)L_GN);
   hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.dE, B.g, vo, B.ls, kBatchLs, (int)L_SLOPE);
@@ -911,9 +1061,13 @@ static rc_status b_step(rc_ctx* c, double* gamma, const rc_batch_opts& o, int ch
                          (const double*)B.phib, (const double*)B.phiq, -1.0, B.yb, B.yq);
       hipLaunchKernelGGL(k_b_apply_ct, dim3(cdiv(nV, 256)), bv, 0, s, B.Jv, B.Lv, iv, B.chain_of_vertex, B.yb, B.yq,
                          (const double*)nullptr, -1.0, nV, B.inc);
-      // y = (P A P)^+ P A z, increment = z - y
-      RC_TRY(launch_sobolev(cv, c->alpha, c->beta, RC_F32, B.inc, B.b, nullptr, s));
-      RC_TRY(b_pcg(c, B.b, B.t, o.proj_tol, o.proj_max_iter, 0));
+      // y = (P A P)^+ P A z, increment = z - y (instances still searching)
+      hipLaunchKernelGGL(k_b_mask_ls, gi, bi, 0, s, B.ls, B.n_inst, B.mask);
+      cv.inst_mask = B.mask;
+      const rc_status so = launch_sobolev(cv, c->alpha, c->beta, RC_F32, B.inc, B.b, nullptr, s);
+      cv.inst_mask = nullptr;
+      RC_TRY(so);
+      RC_TRY(b_pcg(c, B.b, B.t, o.proj_tol, o.proj_max_iter, 0, B.ls));
       vec_axpby(-1.0, B.t, 1.0, B.inc, n3, s);
       hipLaunchKernelGGL(k_b_add_inc, gv, bv, 0, s, iv, B.ls, nV, B.inc, B.trial);
     }
@@ -922,7 +1076,11 @@ static rc_status b_step(rc_ctx* c, double* gamma, const rc_batch_opts& o, int ch
                        B.chain_inst, B.x0, B.L0, B.phiq, B.cq);
     hipLaunchKernelGGL(k_b_phi_inst, gi, bi, 0, s, B.cq, B.phiq, B.L0, B.inst_qoff, B.n_inst, B.phib, B.ls);
     RC_TRY(launch_geometry(cv, B.trial, RC_F32, s));
-    RC_TRY(launch_tpe(cv, c->alpha, c->beta, RC_F32, false, nullptr, nullptr, s));
+    hipLaunchKernelGGL(k_b_mask_ls, gi, bi, 0, s, B.ls, B.n_inst, B.mask);
+    cv.inst_mask = B.mask;
+    const rc_status se = launch_tpe(cv, c->alpha, c->beta, RC_F32, false, nullptr, nullptr, s);
+    cv.inst_mask = nullptr;
+    RC_TRY(se);
     hipLaunchKernelGGL(k_b_edge_sum, dim3(B.n_inst), bv, 0, s, cv.edge_out, 0, cv.inst_eoff, B.energy);
     hipLaunchKernelGGL(k_b_accept, gi, bi, 0, s, B.ls, B.energy, B.n_inst, o.c_armijo, o.accept_tol);
     hipLaunchKernelGGL(k_b_commit, gv, bv, 0, s, iv, B.ls, nV, B.trial, gamma, round);
@@ -982,6 +1140,143 @@ rc_status batch_step(rc_ctx* c, double* gamma, const rc_batch_opts& o, double* s
     RC_HIP(hipMemcpyAsync(stats_h, B.stats, sizeof(double) * 8 * B.n_inst, hipMemcpyDeviceToHost, c->stream));
     RC_HIP(hipStreamSynchronize(c->stream));
   }
+  return RC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tile autotuner for the persistent pair kernels
+// ---------------------------------------------------------------------------
+// Candidates: source ranges of 512 .. 4096 edges and 4, 8 or 16 persistent
+// workgroups per compute unit; each is timed (HIP events, after one warm-up)
+// on one energy + differential and one operator application of the batch at
+// gamma, and the fastest is kept.  Results are cached in a flat JSON object
+// {"<arch>|batch_pairs|E<log2 edges>|I<log2 instances>": [src, blocks, ms], ...}
+// so a later context of the same size class skips the timing.
+void batch_invalidate_graph(rc_ctx* c) {
+  Batch& B = c->batch;
+  if (B.exec) hipGraphExecDestroy(B.exec);
+  if (B.graph) hipGraphDestroy(B.graph);
+  B.exec = nullptr;
+  B.graph = nullptr;
+  B.captured = false;
+}
+
+static std::string tune_key(const rc_ctx* c) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+  }
+  const int le = (int)std::lround(std::log2(std::max(1, c->nE)));
+  const int li = (int)std::lround(std::log2(std::max(1, c->curve.n_inst)));
+  return arch + "|batch_pairs|E" + std::to_string(le) + "|I" + std::to_string(li);
+}
+
+static bool cache_lookup(const char* path, const std::string& key, int* src, int* bpc, double* ms) {
+  if (!path) return false;
+  std::ifstream f(path);
+  if (!f) return false;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string text = ss.str();
+  const std::string pat = "\"" + key + "\"";
+  const size_t k = text.find(pat);
+  if (k == std::string::npos) return false;
+  const size_t b = text.find('[', k);
+  if (b == std::string::npos) return false;
+  return std::sscanf(text.c_str() + b, "[%d, %d, %lf]", src, bpc, ms) == 3;
+}
+
+static void cache_store(const char* path, const std::string& key, int src, int bpc, double ms) {
+  if (!path) return;
+  std::vector<std::string> lines;
+  {
+    std::ifstream f(path);
+    std::string ln;
+    const std::string pat = "\"" + key + "\"";
+    while (f && std::getline(f, ln)) {
+      if (ln.find("\"") == std::string::npos || ln.find(pat) != std::string::npos) continue;
+      while (!ln.empty() && (ln.back() == ',' || ln.back() == ' ')) ln.pop_back();
+      lines.push_back(ln);
+    }
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %.4f]", key.c_str(), src, bpc, ms);
+  lines.push_back(buf);
+  std::ofstream o(path, std::ios::trunc);
+  o << "{\n";
+  for (size_t i = 0; i < lines.size(); ++i) o << lines[i] << (i + 1 < lines.size() ? ",\n" : "\n");
+  o << "}\n";
+}
+
+rc_status batch_autotune(rc_ctx* c, const double* gamma, const char* cache, int* src_out, int* bpc_out,
+                         double* ms_out) {
+  Batch& B = c->batch;
+  Curve& cv = c->curve;
+  hipStream_t s = c->stream;
+  batch_invalidate_graph(c);
+  const std::string key = tune_key(c);
+  int src = 0, bpc = 0;
+  double ms = 0.0;
+  if (cache_lookup(cache, key, &src, &bpc, &ms)) {
+    RC_HIP(hipStreamSynchronize(s));
+    RC_TRY(cv.build_items(src, bpc));
+    *src_out = src;
+    *bpc_out = bpc;
+    *ms_out = ms;
+    return RC_OK;
+  }
+  RC_TRY(launch_geometry(cv, gamma, RC_F32, s));
+  hipEvent_t e0, e1;
+  RC_HIP(hipEventCreate(&e0));
+  RC_HIP(hipEventCreate(&e1));
+  KernelTimer* keep = cv.timer;
+  cv.timer = nullptr;
+  double best = 1e300;
+  int bsrc = 1024, bbpc = 8;
+  rc_status st = RC_OK;
+  const int srcs[] = {512, 1024, 2048, 4096};
+  const int bpcs[] = {4, 8, 16};
+  for (int sc : srcs) {
+    for (int bp : bpcs) {
+      // the item list and partial sums are reallocated: nothing may still read them
+      if (hipStreamSynchronize(s) != hipSuccess) {
+        st = RC_ERR_HIP;
+        break;
+      }
+      if ((st = cv.build_items(sc, bp)) != RC_OK) break;
+      for (int rep = 0; rep < 3 && st == RC_OK; ++rep) {
+        if (rep == 1) hipEventRecord(e0, s);
+        if ((st = launch_tpe(cv, c->alpha, c->beta, RC_F32, true, nullptr, B.dE, s)) != RC_OK) break;
+        st = launch_sobolev(cv, c->alpha, c->beta, RC_F32, gamma, B.t, nullptr, s);
+      }
+      if (st != RC_OK) break;
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float t = 0.f;
+      hipEventElapsedTime(&t, e0, e1);
+      const double per = 0.5 * (double)t;
+      if (per < best) {
+        best = per;
+        bsrc = sc;
+        bbpc = bp;
+      }
+    }
+    if (st != RC_OK) break;
+  }
+  cv.timer = keep;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  RC_TRY(st);
+  RC_HIP(hipStreamSynchronize(s));
+  RC_TRY(cv.build_items(bsrc, bbpc));
+  cache_store(cache, key, bsrc, bbpc, best);
+  *src_out = bsrc;
+  *bpc_out = bbpc;
+  *ms_out = best;
   return RC_OK;
 }
 

@@ -176,9 +176,11 @@ template <typename R, int EC, bool GRAD, bool BAND>
 __global__ __launch_bounds__(kTile) void k_tpe_items(
     const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB, const V4<R>* __restrict__ GT,
     const int2* __restrict__ edges, const int4* __restrict__ cinfo, int nE, const int4* __restrict__ items,
-    int n_items, int* __restrict__ counter, R half_alpha, R half_beta, R beta, double* __restrict__ part) {
+    int n_items, int* __restrict__ counter, const int* __restrict__ inst_of_edge, const int* __restrict__ mask,
+    R half_alpha, R half_beta, R beta, double* __restrict__ part) {
   for (int it = next_item(counter); it < n_items; it = next_item(counter)) {
     const int4 w = items[it];
+    if (mask && !mask[inst_of_edge[w.x]]) continue;  // instance switched off: its partials are not needed
     tpe_tile<R, EC, GRAD, BAND>(GA, GB, GT, edges, cinfo, nE, w.x, w.w & 0xffff, w.y, w.z, w.w >> 16, half_alpha,
                                 half_beta, beta, part);
   }
@@ -191,9 +193,11 @@ template <int EC, bool GRAD>
 __global__ void k_tpe_band(const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB,
                            const V4<double>* __restrict__ GT, const int2* __restrict__ edges,
                            const int4* __restrict__ cinfo, const int* __restrict__ chain_edge, int nE,
-                           double half_alpha, double half_beta, double beta, int chunk, double* __restrict__ part) {
+                           double half_alpha, double half_beta, double beta, int chunk, const int* __restrict__ inst_of_edge,
+                           const int* __restrict__ mask, double* __restrict__ part) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nE) return;
+  if (mask && !mask[inst_of_edge[I]]) return;
   const V4<double> a = GA[I], b = GB[I], t = GT[I];
   const int2 ei = edges[I];
   const int4 ci = cinfo[I];
@@ -442,9 +446,11 @@ template <typename R, int EC>
 __global__ __launch_bounds__(kTile) void k_sob_items(
     const V4<R>* __restrict__ GA, const V4<R>* __restrict__ GB, const V4<R>* __restrict__ GT,
     const int2* __restrict__ edges, const V4<R>* __restrict__ RS, const V4<R>* __restrict__ RU, int nE,
-    const int4* __restrict__ items, int n_items, int* __restrict__ counter, R half_expo, double* __restrict__ part) {
+    const int4* __restrict__ items, int n_items, int* __restrict__ counter, const int* __restrict__ inst_of_edge,
+    const int* __restrict__ mask, R half_expo, double* __restrict__ part) {
   for (int it = next_item(counter); it < n_items; it = next_item(counter)) {
     const int4 w = items[it];
+    if (mask && !mask[inst_of_edge[w.x]]) continue;
     sob_tile<R, EC>(GA, GB, GT, edges, RS, RU, nE, w.x, w.w & 0xffff, w.y, w.z, w.w >> 16, half_expo, part);
   }
 }
@@ -797,16 +803,17 @@ static void run_tpe(const Curve& c, const EdgeGeom<R>& g, double alpha, double b
     if (timed) c.timer->mark(c.timer->tpe, s);
     if (band)
       hipLaunchKernelGGL((k_tpe_items<R, EC, GRAD, true>), dim3(c.persist_blocks), dim3(kTile), 0, s, g.a, g.b, g.t,
-                         c.edges, c.cinfo, c.nE, c.items, c.n_items, c.counter, R(0.5 * alpha), R(0.5 * beta),
-                         R(beta), c.part);
+                         c.edges, c.cinfo, c.nE, c.items, c.n_items, c.counter, c.inst_of_edge, c.inst_mask,
+                         R(0.5 * alpha), R(0.5 * beta), R(beta), c.part);
     else
       hipLaunchKernelGGL((k_tpe_items<R, EC, GRAD, false>), dim3(c.persist_blocks), dim3(kTile), 0, s, g.a, g.b,
-                         g.t, c.edges, c.cinfo, c.nE, c.items, c.n_items, c.counter, R(0.5 * alpha), R(0.5 * beta),
-                         R(beta), c.part);
+                         g.t, c.edges, c.cinfo, c.nE, c.items, c.n_items, c.counter, c.inst_of_edge, c.inst_mask,
+                         R(0.5 * alpha), R(0.5 * beta), R(beta), c.part);
     if (timed) c.timer->mark(c.timer->tpe, s);
     if (band)
       hipLaunchKernelGGL((k_tpe_band<EC, GRAD>), dim3(cdiv(c.nE, 64)), dim3(64), 0, s, c.gd.a, c.gd.b, c.gd.t,
-                         c.edges, c.cinfo, c.chain_edge, c.nE, 0.5 * alpha, 0.5 * beta, beta, c.nchunk, c.part);
+                         c.edges, c.cinfo, c.chain_edge, c.nE, 0.5 * alpha, 0.5 * beta, beta, c.nchunk, c.inst_of_edge,
+                         c.inst_mask, c.part);
     return;
   }
   if (band) {
@@ -815,7 +822,8 @@ static void run_tpe(const Curve& c, const EdgeGeom<R>& g, double alpha, double b
                        c.nE, c.src_per_chunk, R(0.5 * alpha), R(0.5 * beta), R(beta), c.part);
     if (timed) c.timer->mark(c.timer->tpe, s);
     hipLaunchKernelGGL((k_tpe_band<EC, GRAD>), dim3(cdiv(c.nE, 64)), dim3(64), 0, s, c.gd.a, c.gd.b, c.gd.t,
-                       c.edges, c.cinfo, c.chain_edge, c.nE, 0.5 * alpha, 0.5 * beta, beta, c.nchunk, c.part);
+                       c.edges, c.cinfo, c.chain_edge, c.nE, 0.5 * alpha, 0.5 * beta, beta, c.nchunk, c.inst_of_edge,
+                         c.inst_mask, c.part);
   } else {
     if (timed) c.timer->mark(c.timer->tpe, s);
     hipLaunchKernelGGL((k_tpe_pairs<R, EC, GRAD, false>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges,
@@ -869,7 +877,8 @@ static void run_sob(const Curve& c, const EdgeGeom<R>& g, V4<R>* const* rhs, dou
   if (timed) c.timer->mark(c.timer->sob, s);
   if (c.n_inst > 0)
     hipLaunchKernelGGL((k_sob_items<R, EC>), dim3(c.persist_blocks), dim3(kTile), 0, s, g.a, g.b, g.t, c.edges,
-                       rhs[0], rhs[1], c.nE, c.items, c.n_items, c.counter, R(half_expo), c.part);
+                       rhs[0], rhs[1], c.nE, c.items, c.n_items, c.counter, c.inst_of_edge, c.inst_mask,
+                       R(half_expo), c.part);
   else
     hipLaunchKernelGGL((k_sob_pairs<R, EC>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, rhs[0], rhs[1],
                        c.nE, c.src_per_chunk, R(half_expo), c.part);

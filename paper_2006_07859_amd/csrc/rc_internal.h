@@ -149,6 +149,7 @@ struct Curve {
   int n_items = 0, item_src = 0, persist_blocks = 0, blocks_per_cu = 0;
   int* nch_e = nullptr;
   int* counter = nullptr;
+  const int* inst_mask = nullptr;  // when set, work items of instances with mask 0 are skipped
   Obstacle obstacle;               // applied by launch_tpe when on
 
   rc_status init(int nV_, int nE_, const int* edges_h);

@@ -76,6 +76,11 @@ struct Batch {
   double *sc = nullptr, *ls = nullptr, *energy = nullptr, *stats = nullptr;
   double *trial = nullptr, *ghat = nullptr, *dE = nullptr, *g = nullptr, *inc = nullptr;
   double *phiq = nullptr, *phib = nullptr;
+  int* mask = nullptr;             // per-instance work mask of the pair kernels
+  int gj_steps = 0, n_prec = 0;
+  std::vector<int> h_gj_step_off, h_gj_tiles;
+  int *gj_list = nullptr, *gj_pre = nullptr;
+  int2* prec_items = nullptr;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -150,5 +155,8 @@ rc_status batch_edge_sums(rc_ctx* c, int slot, double* out);
 rc_status batch_set_constraints(rc_ctx* c, const double* gamma_ref);
 rc_status batch_gradient(rc_ctx* c, const double* gamma, const double* dE, double* g, const rc_batch_opts& o);
 rc_status batch_step(rc_ctx* c, double* gamma, const rc_batch_opts& o, double* stats_h);
+void batch_invalidate_graph(rc_ctx* c);
+rc_status batch_autotune(rc_ctx* c, const double* gamma, const char* cache, int* src_out, int* bpc_out,
+                         double* ms_out);
 
 }  // namespace rc

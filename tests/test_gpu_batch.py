@@ -211,3 +211,23 @@ def test_full_batch_512(lib):
     assert ok.sum() >= 500
     assert np.all(st[ok, 1] < st[ok, 0])
     b.close()
+
+
+def test_autotune_and_cache(lib, tmp_path):
+    insts = small_batch(n=8, seed=13, e_max=2000)
+    banner("batch tile autotuner with cache")
+    b, g, e, voff = make_batch(insts)
+    gam = dev(g)
+    En0 = zeros(len(insts))
+    b.rc_batch_energies(gam, En0)
+    cache = tmp_path / "tune.json"
+    t1 = b.rc_batch_autotune(gam, cache)
+    assert t1["src_chunk"] in (512, 1024, 2048, 4096) and t1["blocks_per_cu"] in (4, 8, 16) and t1["ms"] > 0
+    assert cache.exists() and "batch_pairs" in cache.read_text()
+    t2 = b.rc_batch_autotune(gam, cache)  # cache hit: same choice
+    assert (t2["src_chunk"], t2["blocks_per_cu"]) == (t1["src_chunk"], t1["blocks_per_cu"])
+    En1 = zeros(len(insts))
+    b.rc_batch_energies(gam, En1)
+    # a different tiling changes only the summation order of the FP64-folded partials
+    assert np.allclose(host(En1), host(En0), rtol=1e-6, atol=0)
+    b.close()
