@@ -577,8 +577,8 @@ extern "C" void rc_default_batch_opts(rc_batch_opts* o) {
   o->max_iter = 120;
   o->ls_rounds = 4;
   o->proj_iters = 2;
-  o->proj_max_iter = 20;
-  o->proj_tol = 1e-3;
+  o->proj_max_iter = 10;
+  o->proj_tol = 1e-2;
   o->accept_tol = 1e-6;
   o->c_armijo = 0.01;
   o->tau0 = 1.0;
