@@ -36,6 +36,7 @@ extern "C" {
 #endif
 
 typedef struct rc_ctx rc_ctx;
+typedef struct rc_mlp rc_mlp;
 typedef void* rc_stream; /* a hipStream_t; NULL = the null stream */
 
 typedef enum {
@@ -66,7 +67,11 @@ enum {
 typedef enum {
   RC_SOLVE_DENSE = 0,    /* assembled FP64 A, Cholesky of Abar + C^T C, Schur complement */
   RC_SOLVE_PCG_JACOBI = 1, /* matrix-free projected PCG, Jacobi preconditioner */
-  RC_SOLVE_PCG_MG = 2    /* matrix-free projected PCG, multigrid V-cycle preconditioner */
+  RC_SOLVE_PCG_MG = 2,   /* matrix-free projected PCG, multigrid V-cycle preconditioner */
+  RC_SOLVE_PCG_MULTILEVEL = 3, /* additive multilevel preconditioner sum_l P_l D_l P_l^T over the
+                                  multigrid levels, D_l = diag(A_l)^-1 (hand-weighted) */
+  RC_SOLVE_PCG_LEARNED = 4     /* the same with D_l = diag(y_l / diag(A_l)), y_l from the MLP attached
+                                  by rc_learned_attach */
 } rc_solver;
 
 typedef struct {
@@ -353,6 +358,67 @@ rc_status rc_batch_step(rc_ctx* ctx, double* gamma, const rc_batch_opts* opts, d
 /* Iterations and relative residual of every instance in the last batch PCG
  * solve (host double[n_inst] each); synchronises. */
 rc_status rc_batch_pcg_state(rc_ctx* ctx, double* iters_h, double* res_h);
+
+/* ------------------------------------------------------------------------
+ * Learned multilevel preconditioner.  For a single closed loop whose
+ * vertices are numbered along it, M^-1 = sum_l P_l D_l P_l^T over the
+ * multigrid levels (the black/white hierarchy of App. B.3.1, P_l the chained
+ * prolongations), with D_l = diag(y_{l,v} / diag(A_l)_v) and y > 0 the output
+ * of an MLP (8 -> 64 -> 64 -> 1, ReLU, softplus) on per-vertex features.
+ * Symmetric positive definite for any weights; PCG applies P M^-1 P.
+ * ---------------------------------------------------------------------- */
+
+/* Number of MLP parameters (4,801), flat order W1 [8][64], b1 [64],
+ * W2 [64][64], b2 [64], W3 [64], b3 [1]. */
+int32_t rc_mlp_n_params(void);
+
+/* Creates an MLP on `stream` with parameters theta_h (host float[n_params],
+ * NULL = zeros).  Weights are held in FP32 (master, Adam state) and FP16
+ * (used by the forward pass); biases in FP32. */
+rc_status rc_mlp_create(const float* theta_h, rc_stream stream, rc_mlp** out);
+rc_status rc_mlp_destroy(rc_mlp* mlp);
+/* Copies the FP32 parameters to / from the host; set also resets Adam. */
+rc_status rc_mlp_get(rc_mlp* mlp, float* theta_h);
+rc_status rc_mlp_set(rc_mlp* mlp, const float* theta_h);
+/* Y = y(X) for N rows: X device float[N][8], Y device float[N]. */
+rc_status rc_mlp_forward(rc_mlp* mlp, const float* X, int32_t N, float* Y);
+/* grad = d(sum_r dY[r] y(X[r]))/dtheta (device float[n_params]); runs the
+ * forward pass itself.  X, dY: device float. */
+rc_status rc_mlp_backward(rc_mlp* mlp, const float* X, int32_t N, const float* dY, float* grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the gradient grad
+ * (device float[n_params]) and learning rate lr > 0. */
+rc_status rc_mlp_adam(rc_mlp* mlp, const float* grad, float lr);
+
+/* Attaches mlp (NULL detaches) to the context for RC_SOLVE_PCG_LEARNED and
+ * the rc_learned_* calls; the caller keeps ownership. */
+rc_status rc_learned_attach(rc_ctx* ctx, rc_mlp* mlp);
+
+/* Level sizes of the hierarchy for coarsest size n_min (sizes_h: host
+ * int32[max_levels]); returns the number of levels in *levels. */
+rc_status rc_learned_levels(rc_ctx* ctx, int32_t n_min, int32_t* sizes_h, int32_t max_levels, int32_t* levels);
+
+/* Features of every level at gamma (levels stacked, finest first): X device
+ * float[N][8] with N the sum of the level sizes; diag (optional) device
+ * double[N] the level diagonals.  RC_ERR_UNSUPPORTED unless the curve is one
+ * closed loop numbered along itself. */
+rc_status rc_learned_features(rc_ctx* ctx, const double* gamma, int32_t n_min, float* X, double* diag);
+
+/* The scalings D_l (device double[N], levels stacked) at gamma: y / diag with
+ * y from the attached MLP, or 1 / diag without one. */
+rc_status rc_learned_scalings(rc_ctx* ctx, const double* gamma, int32_t n_min, double* scal);
+
+/* Y = P M^-1 P X at gamma (device double[nV][3]); the constraints must be set. */
+rc_status rc_learned_apply(rc_ctx* ctx, const double* gamma, int32_t n_min, const double* X, double* Y);
+
+/* One training sample: loss = 1 - <z, g>_A^2 / (|z|_A^2 |g|_A^2) with
+ * z = P M^-1 P dE and g = g_ref the projected gradient (the relative A-norm
+ * error of the best-scaled application), its gradient through the MLP
+ * (written to grad, device float[n_params], when grad is not NULL) and, when
+ * lr > 0, one Adam step of the attached MLP.  A is the matrix-free FP32
+ * operator; the constraints must be set.  gamma, dE, g_ref: device
+ * double[nV][3]; *loss_h receives the loss.  Synchronises the stream. */
+rc_status rc_learned_train_step(rc_ctx* ctx, const double* gamma, const double* dE, const double* g_ref,
+                                int32_t n_min, float lr, double* loss_h, float* grad);
 
 /* Kernel timing with HIP events on the context's stream.  rc_profile_enable
  * clears earlier records and, when enable != 0, brackets every launch of the

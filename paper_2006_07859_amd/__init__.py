@@ -14,12 +14,16 @@ from ._lib import (  # noqa: F401
     RC_F64,
     RC_SOLVE_DENSE,
     RC_SOLVE_PCG_JACOBI,
+    RC_SOLVE_PCG_LEARNED,
     RC_SOLVE_PCG_MG,
+    RC_SOLVE_PCG_MULTILEVEL,
     Batch,
     Context,
+    Mlp,
     RcError,
     default_batch_opts,
     default_ls_opts,
     default_solve_opts,
     load,
+    mlp_n_params,
 )

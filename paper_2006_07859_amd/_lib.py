@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "librcurves.so")
 
 RC_F64, RC_F32 = 0, 1
 RC_C_BARYCENTER, RC_C_TOTAL_LENGTH, RC_C_EDGE_LENGTH = 1, 2, 4
-RC_SOLVE_DENSE, RC_SOLVE_PCG_JACOBI, RC_SOLVE_PCG_MG = 0, 1, 2
+RC_SOLVE_DENSE, RC_SOLVE_PCG_JACOBI, RC_SOLVE_PCG_MG, RC_SOLVE_PCG_MULTILEVEL, RC_SOLVE_PCG_LEARNED = 0, 1, 2, 3, 4
 
 STATUS = {
     0: "RC_OK", 1: "RC_ERR_ARG", 2: "RC_ERR_PARAM_RANGE", 3: "RC_ERR_DEGENERATE", 4: "RC_ERR_NONFINITE",
@@ -34,6 +34,9 @@ EXPORTED = [
     "rc_profile_enable", "rc_profile_read", "rc_lowp_assemble", "rc_lowp_apply", "rc_set_obstacle",
     "rc_create_batch", "rc_batch_size", "rc_batch_energies", "rc_batch_tiling", "rc_default_batch_opts",
     "rc_batch_set_constraints", "rc_batch_gradient", "rc_batch_step", "rc_batch_pcg_state", "rc_batch_autotune",
+    "rc_mlp_n_params", "rc_mlp_create", "rc_mlp_destroy", "rc_mlp_get", "rc_mlp_set", "rc_mlp_forward",
+    "rc_mlp_backward", "rc_mlp_adam", "rc_learned_attach", "rc_learned_levels", "rc_learned_features",
+    "rc_learned_scalings", "rc_learned_apply", "rc_learned_train_step",
 ]
 
 
@@ -123,6 +126,20 @@ def load():
         "rc_batch_pcg_state": (I32, [P, P, P]),
         "rc_batch_autotune": (I32, [P, P, C.c_char_p, C.POINTER(I32), C.POINTER(I32), C.POINTER(D)]),
         "rc_lowp_apply": (I32, [P, P, P, I32]),
+        "rc_mlp_n_params": (I32, []),
+        "rc_mlp_create": (I32, [P, P, C.POINTER(P)]),
+        "rc_mlp_destroy": (I32, [P]),
+        "rc_mlp_get": (I32, [P, P]),
+        "rc_mlp_set": (I32, [P, P]),
+        "rc_mlp_forward": (I32, [P, P, I32, P]),
+        "rc_mlp_backward": (I32, [P, P, I32, P, P]),
+        "rc_mlp_adam": (I32, [P, P, C.c_float]),
+        "rc_learned_attach": (I32, [P, P]),
+        "rc_learned_levels": (I32, [P, I32, P, I32, C.POINTER(I32)]),
+        "rc_learned_features": (I32, [P, P, I32, P, P]),
+        "rc_learned_scalings": (I32, [P, P, I32, P]),
+        "rc_learned_apply": (I32, [P, P, I32, P, P]),
+        "rc_learned_train_step": (I32, [P, P, P, P, I32, C.c_float, C.POINTER(D), P]),
     }
     for name, (res, args) in sig.items():
         if not hasattr(lib, name):
@@ -309,6 +326,105 @@ class Context:
         f, n, nodes, depth = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32()
         _check(load().rc_bh_last_work(self.h, C.byref(f), C.byref(n), C.byref(nodes), C.byref(depth)))
         return {"far": f.value, "near": n.value, "nodes": nodes.value, "depth": depth.value}
+
+    # learned multilevel preconditioner
+    def rc_learned_attach(self, mlp):
+        self._mlp = mlp  # the context does not own it: keep it alive
+        _check(load().rc_learned_attach(self.h, None if mlp is None else mlp.h))
+
+    def rc_learned_levels(self, n_min):
+        sizes, nl = (C.c_int32 * 64)(), C.c_int32()
+        _check(load().rc_learned_levels(self.h, int(n_min), C.cast(sizes, C.c_void_p), 64, C.byref(nl)))
+        return [sizes[i] for i in range(nl.value)]
+
+    def rc_learned_features(self, gamma, n_min, X, diag=None):
+        import torch
+
+        N = sum(self.rc_learned_levels(n_min))
+        _check(load().rc_learned_features(self.h, self._v(gamma, "gamma"), int(n_min),
+                                          _ptr(X, (N, 8), torch.float32, "X"),
+                                          None if diag is None else _ptr(diag, (N,), self._f64, "diag")))
+
+    def rc_learned_scalings(self, gamma, n_min, scal):
+        N = sum(self.rc_learned_levels(n_min))
+        _check(load().rc_learned_scalings(self.h, self._v(gamma, "gamma"), int(n_min),
+                                          _ptr(scal, (N,), self._f64, "scal")))
+
+    def rc_learned_apply(self, gamma, n_min, X, Y):
+        _check(load().rc_learned_apply(self.h, self._v(gamma, "gamma"), int(n_min), self._v(X, "X"),
+                                       self._v(Y, "Y")))
+
+    def rc_learned_train_step(self, gamma, dE, g_ref, n_min, lr, grad=None):
+        import torch
+
+        loss = C.c_double()
+        _check(load().rc_learned_train_step(self.h, self._v(gamma, "gamma"), self._v(dE, "dE"),
+                                            self._v(g_ref, "g_ref"), int(n_min), float(lr), C.byref(loss),
+                                            None if grad is None else _ptr(grad, (mlp_n_params(),), torch.float32,
+                                                                           "grad")))
+        return loss.value
+
+
+def mlp_n_params():
+    return int(load().rc_mlp_n_params())
+
+
+class Mlp:
+    """Owns one rc_mlp (the network of the learned preconditioner) on the current stream."""
+
+    def __init__(self, theta=None):
+        lib = load()
+        self.n = mlp_n_params()
+        h = C.c_void_p()
+        t = None
+        if theta is not None:
+            t = np.ascontiguousarray(np.asarray(theta, dtype=np.float32))
+            if t.shape != (self.n,):
+                raise ValueError(f"theta must have {self.n} entries")
+        _check(lib.rc_mlp_create(None if t is None else t.ctypes.data_as(C.c_void_p), _stream(), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().rc_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get(self):
+        out = np.zeros(self.n, dtype=np.float32)
+        _check(load().rc_mlp_get(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set(self, theta):
+        t = np.ascontiguousarray(np.asarray(theta, dtype=np.float32))
+        if t.shape != (self.n,):
+            raise ValueError(f"theta must have {self.n} entries")
+        _check(load().rc_mlp_set(self.h, t.ctypes.data_as(C.c_void_p)))
+
+    def forward(self, X, Y):
+        import torch
+
+        N = int(X.shape[0])
+        _check(load().rc_mlp_forward(self.h, _ptr(X, (N, 8), torch.float32, "X"), N,
+                                     _ptr(Y, (N,), torch.float32, "Y")))
+
+    def backward(self, X, dY, grad):
+        import torch
+
+        N = int(X.shape[0])
+        _check(load().rc_mlp_backward(self.h, _ptr(X, (N, 8), torch.float32, "X"), N,
+                                      _ptr(dY, (N,), torch.float32, "dY"),
+                                      _ptr(grad, (self.n,), torch.float32, "grad")))
+
+    def adam(self, grad, lr):
+        import torch
+
+        _check(load().rc_mlp_adam(self.h, _ptr(grad, (self.n,), torch.float32, "grad"), float(lr)))
 
 
 class Batch(Context):

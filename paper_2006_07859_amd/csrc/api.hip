@@ -191,6 +191,7 @@ rc_status rc_destroy(rc_ctx* c) {
   c->timer.clear();
   c->bvh.release();
   c->lowp.release();
+  learn_free(c);
   batch_free(c);
   mg_free(c);
   dense_free(c->dense);
@@ -645,4 +646,151 @@ extern "C" rc_status rc_batch_pcg_state(rc_ctx* c, double* iters_h, double* res_
     res_h[i] = sc[(size_t)i * kBatchScal + 6];
   }
   return RC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned multilevel preconditioner
+// ---------------------------------------------------------------------------
+extern "C" int32_t rc_mlp_n_params(void) { return kMlpParams; }
+
+extern "C" rc_status rc_mlp_create(const float* theta_h, rc_stream stream, rc_mlp** out) {
+  RC_TRY(check_ptrs({out}));
+  *out = nullptr;
+  auto* m = new (std::nothrow) rc_mlp();
+  if (!m) {
+    set_error("out of host memory");
+    return RC_ERR_NOMEM;
+  }
+  rc_status st = m->m.init(theta_h, (hipStream_t)stream);
+  if (st != RC_OK) {
+    m->m.release();
+    delete m;
+    return st;
+  }
+  *out = m;
+  return RC_OK;
+}
+
+extern "C" rc_status rc_mlp_destroy(rc_mlp* m) {
+  if (!m) return RC_OK;
+  hipStreamSynchronize(m->m.stream);
+  m->m.release();
+  delete m;
+  return RC_OK;
+}
+
+static rc_status check_mlp(const rc_mlp* m) {
+  if (!m) {
+    set_error("null MLP");
+    return RC_ERR_ARG;
+  }
+  return RC_OK;
+}
+
+extern "C" rc_status rc_mlp_get(rc_mlp* m, float* theta_h) {
+  RC_TRY(check_mlp(m));
+  RC_TRY(check_ptrs({theta_h}));
+  RC_HIP(hipStreamSynchronize(m->m.stream));
+  RC_HIP(hipMemcpy(theta_h, m->m.theta, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+  return RC_OK;
+}
+
+extern "C" rc_status rc_mlp_set(rc_mlp* m, const float* theta_h) {
+  RC_TRY(check_mlp(m));
+  RC_TRY(check_ptrs({theta_h}));
+  RC_HIP(hipStreamSynchronize(m->m.stream));
+  return m->m.set(theta_h);
+}
+
+extern "C" rc_status rc_mlp_forward(rc_mlp* m, const float* X, int32_t N, float* Y) {
+  RC_TRY(check_mlp(m));
+  if (N < 0) {
+    set_error("rc_mlp_forward: N < 0");
+    return RC_ERR_ARG;
+  }
+  if (N == 0) return RC_OK;
+  RC_TRY(check_ptrs({X, Y}));
+  return mlp_forward(m->m, X, N, Y, false, m->m.stream);
+}
+
+extern "C" rc_status rc_mlp_backward(rc_mlp* m, const float* X, int32_t N, const float* dY, float* grad) {
+  RC_TRY(check_mlp(m));
+  RC_TRY(check_ptrs({X, dY, grad}));
+  if (N <= 0) {
+    set_error("rc_mlp_backward: N must be positive");
+    return RC_ERR_ARG;
+  }
+  RC_TRY(m->m.ensure_rows(N));  // allocates the output row buffer Y before it is passed on
+  RC_TRY(mlp_forward(m->m, X, N, m->m.Y, true, m->m.stream));
+  return mlp_backward(m->m, X, N, dY, grad, m->m.stream);
+}
+
+extern "C" rc_status rc_mlp_adam(rc_mlp* m, const float* grad, float lr) {
+  RC_TRY(check_mlp(m));
+  RC_TRY(check_ptrs({grad}));
+  if (!(lr > 0.f)) {
+    set_error("rc_mlp_adam: lr must be positive");
+    return RC_ERR_ARG;
+  }
+  return mlp_adam(m->m, grad, lr, m->m.stream);
+}
+
+extern "C" rc_status rc_learned_attach(rc_ctx* c, rc_mlp* m) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_learned_attach"));
+  c->mlp = m;
+  return RC_OK;
+}
+
+extern "C" rc_status rc_learned_levels(rc_ctx* c, int32_t n_min, int32_t* sizes_h, int32_t max_levels,
+                                       int32_t* levels) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_learned_levels"));
+  RC_TRY(check_ptrs({levels}));
+  RC_TRY(learn_prepare_levels(c, n_min));
+  const int nl = (int)c->learn_off.size() - 1;
+  *levels = nl;
+  for (int l = 0; sizes_h && l < nl && l < max_levels; ++l) sizes_h[l] = c->learn_off[l + 1] - c->learn_off[l];
+  return RC_OK;
+}
+
+extern "C" rc_status rc_learned_features(rc_ctx* c, const double* gamma, int32_t n_min, float* X, double* diag) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_learned_features"));
+  RC_TRY(check_ptrs({gamma, X}));
+  RC_TRY(learn_prepare(c, gamma, n_min, false, false));
+  const int N = c->learn_N;
+  RC_HIP(hipMemcpyAsync(X, c->learn_X, sizeof(float) * kMlpIn * N, hipMemcpyDeviceToDevice, c->stream));
+  if (diag) RC_HIP(hipMemcpyAsync(diag, c->learn_diag, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+  return RC_OK;
+}
+
+extern "C" rc_status rc_learned_scalings(rc_ctx* c, const double* gamma, int32_t n_min, double* scal) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_learned_scalings"));
+  RC_TRY(check_ptrs({gamma, scal}));
+  RC_TRY(learn_prepare(c, gamma, n_min, c->mlp != nullptr, false));
+  RC_HIP(hipMemcpyAsync(scal, c->learn_scal, sizeof(double) * c->learn_N, hipMemcpyDeviceToDevice, c->stream));
+  return RC_OK;
+}
+
+extern "C" rc_status rc_learned_apply(rc_ctx* c, const double* gamma, int32_t n_min, const double* X, double* Y) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_learned_apply"));
+  RC_TRY(check_ptrs({gamma, X, Y}));
+  RC_TRY(cons_prepare(c, c->curve, c->cons, gamma));
+  RC_TRY(learn_prepare(c, gamma, n_min, c->mlp != nullptr, false));
+  return learn_apply(c, X, Y);
+}
+
+extern "C" rc_status rc_learned_train_step(rc_ctx* c, const double* gamma, const double* dE, const double* g_ref,
+                                           int32_t n_min, float lr, double* loss_h, float* grad) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_learned_train_step"));
+  RC_TRY(check_ptrs({gamma, dE, g_ref, loss_h}));
+  if (!(lr >= 0.f)) {
+    set_error("rc_learned_train_step: lr must be >= 0");
+    return RC_ERR_ARG;
+  }
+  return learn_train(c, gamma, dE, g_ref, n_min, lr, loss_h, grad);
 }

@@ -232,6 +232,30 @@ rc_status launch_assemble_lowp(const Curve& c, LowpOp& op, int fmt, int band, bo
 rc_status launch_lowp_apply(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer);
 rc_status launch_lowp_apply32(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer);
 
+// Learned multilevel preconditioner (k_learn.hip): the MLP and the features.
+constexpr int kMlpIn = 8, kMlpWidth = 64;
+constexpr int kMlpParams = kMlpIn * kMlpWidth + kMlpWidth + kMlpWidth * kMlpWidth + kMlpWidth + kMlpWidth + 1;
+constexpr int kFeatSep = 4;  // vertices at most this far apart along the loop are not "other parts" of it
+struct Mlp {
+  float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *opart = nullptr;
+  _Float16* w16 = nullptr;
+  float *H1 = nullptr, *H2 = nullptr, *O = nullptr, *Do = nullptr, *D1 = nullptr, *D2 = nullptr;
+  float *Y = nullptr, *dY = nullptr;
+  int cap = 0, t = 0;
+  hipStream_t stream = nullptr;
+  rc_status init(const float* theta_h, hipStream_t s);
+  rc_status set(const float* theta_h);
+  rc_status ensure_rows(int N);
+  void release();
+};
+rc_status mlp_forward(Mlp& M, const float* X, int N, float* Y, bool keep, hipStream_t s);
+rc_status mlp_backward(Mlp& M, const float* X, int N, const float* dY, float* grad, hipStream_t s);
+rc_status mlp_adam(Mlp& M, const float* grad, float lr, hipStream_t s);
+// Features of one level (a loop numbered along itself) into X [n][8];
+// scratch holds 10 n + 2 doubles.
+rc_status launch_level_features(const Curve& cv, const double* gam, const double* diag, int level, int levels,
+                                double* scratch, float* X, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // dense and vector helpers (k_linalg.hip)
 // ---------------------------------------------------------------------------

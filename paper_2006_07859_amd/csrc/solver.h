@@ -118,6 +118,17 @@ struct rc_ctx {
   int lowp_levels = 0, lowp_fmt = 0, lowp_band = 0, lowp_outer = 0;
   int last_sweeps = 0;  // FP64 true-residual evaluations of the last PCG solve
   rc::Batch batch;      // batch contexts only
+  // learned / hand-weighted multilevel preconditioner
+  rc_mlp* mlp = nullptr;          // attached, not owned
+  int learn_nmin = -1, learn_N = 0, learn_cap = 0;
+  std::vector<int> learn_off;     // row offset of every level
+  double *learn_diag = nullptr, *learn_scal = nullptr, *learn_u = nullptr, *learn_w = nullptr, *learn_tmp = nullptr;
+  double* learn_scratch = nullptr;
+  float *learn_X = nullptr, *learn_Y = nullptr, *learn_dY = nullptr;
+};
+
+struct rc_mlp {
+  rc::Mlp m;
 };
 
 namespace rc {
@@ -147,6 +158,13 @@ struct LsResult {
 };
 rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, const double* g, const rc_ls_opts& ls,
                       const rc_solve_opts& so, LsResult* out);
+
+rc_status learn_prepare_levels(rc_ctx* c, int n_min);
+rc_status learn_prepare(rc_ctx* c, const double* gamma, int n_min, bool use_mlp, bool keep);
+rc_status learn_apply(rc_ctx* c, const double* r, double* z);
+rc_status learn_train(rc_ctx* c, const double* gamma, const double* dE, const double* g_ref, int n_min, float lr,
+                      double* loss, float* grad_out);
+void learn_free(rc_ctx* c);
 
 // batch.hip
 rc_status batch_alloc(rc_ctx* c);

@@ -761,7 +761,10 @@ static rc_status vcycle(rc_ctx* c, int l, const double* b, double* x) {
 // ---------------------------------------------------------------------------
 // projected PCG:  P Abar P y = P b, y in range(P)   (App. B.3.3)
 // ---------------------------------------------------------------------------
+rc_status learn_apply(rc_ctx* c, const double* r, double* z);
+
 static rc_status precondition(rc_ctx* c, int kind, const double* r, double* z) {
+  if (kind == RC_SOLVE_PCG_MULTILEVEL || kind == RC_SOLVE_PCG_LEARNED) return learn_apply(c, r, z);
   if (kind == RC_SOLVE_PCG_MG) {
     MGLevelState& st = c->mg[0];
     vec_copy(r, st.b, 3 * c->nV, c->stream);
@@ -858,6 +861,10 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
 // entry points used by the C ABI
 // ---------------------------------------------------------------------------
 rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o) {
+  if (o.solver < RC_SOLVE_DENSE || o.solver > RC_SOLVE_PCG_LEARNED) {
+    set_error("solve options: unknown solver kind");
+    return RC_ERR_ARG;
+  }
   if (o.lowp < 0 || o.lowp > 2) {
     set_error("solve options: lowp must be 0 (off), 1 (BF16) or 2 (FP16)");
     return RC_ERR_ARG;
@@ -873,6 +880,14 @@ rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o)
   c->lowp_fmt = o.lowp;
   c->lowp_band = o.lowp_band;
   c->lowp_outer = o.lowp_outer;
+  if (o.solver == RC_SOLVE_PCG_MULTILEVEL || o.solver == RC_SOLVE_PCG_LEARNED) {
+    if (o.lowp) {
+      set_error("solve options: the 16-bit operator serves the Jacobi and multigrid preconditioners only");
+      return RC_ERR_ARG;
+    }
+    RC_TRY(learn_prepare(c, gamma, o.mg_min_vertices, o.solver == RC_SOLVE_PCG_LEARNED, false));
+    return load_geometry(c, gamma);
+  }
   if (o.solver == RC_SOLVE_PCG_MG) {
     if (c->mg_min != o.mg_min_vertices) {
       mg_free(c);
@@ -1014,6 +1029,215 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
   set_error("line search found no admissible step");
   out->backtracks = ls.max_backtracks;
   return RC_ERR_LINESEARCH;
+}
+
+// ---------------------------------------------------------------------------
+// Multilevel preconditioner M^-1 = sum_l P_l D_l P_l^T over the multigrid
+// hierarchy (P_0 = Id, P_l = J_1 ... J_l), applied as P M^-1 P, with
+// D_l = diag(y_l / diag(A_l)): y = 1 (hand-weighted) or the attached MLP's
+// output on the level features (learned).  Vectors of all levels are stacked
+// finest first, level l at row learn_off[l].
+// ---------------------------------------------------------------------------
+// scal = y / diag (y = null: 1 / diag)
+__global__ void k_learn_scal(const float* __restrict__ y, const double* __restrict__ diag, int N,
+                             double* __restrict__ scal) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) scal[i] = (y ? (double)y[i] : 1.0) / diag[i];
+}
+
+// z_l = scal_l u_l + J_{l+1} z_{l+1} (zc = null on the coarsest level)
+__global__ void k_learn_down(const int2* __restrict__ pr, int n, const double* __restrict__ zc,
+                             const double* __restrict__ scal, const double* __restrict__ u, double* __restrict__ z) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const double d = scal[v];
+  int2 ab = pr ? pr[v] : make_int2(0, 0);
+  for (int k = 0; k < 3; ++k)
+    z[3 * v + k] = d * u[3 * v + k] + (zc ? 0.5 * (zc[3 * ab.x + k] + zc[3 * ab.y + k]) : 0.0);
+}
+
+// dY_i = sum_c w_i,c u_i,c / diag_i: the loss gradient with respect to y
+__global__ void k_learn_dy(const double* __restrict__ w, const double* __restrict__ u, const double* __restrict__ diag,
+                           int N, float* __restrict__ dY) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  dY[i] = (float)((w[3 * i] * u[3 * i] + w[3 * i + 1] * u[3 * i + 1] + w[3 * i + 2] * u[3 * i + 2]) / diag[i]);
+}
+
+void learn_free(rc_ctx* c) {
+  dfree(c->learn_diag);
+  dfree(c->learn_scal);
+  dfree(c->learn_u);
+  dfree(c->learn_w);
+  dfree(c->learn_tmp);
+  dfree(c->learn_scratch);
+  dfree(c->learn_X);
+  dfree(c->learn_Y);
+  dfree(c->learn_dY);
+  c->learn_cap = 0;
+  c->learn_nmin = -1;
+}
+
+// Hierarchy for coarsest size n_min; every level must be one closed loop
+// whose vertices are numbered along it (checked once per hierarchy).
+rc_status learn_prepare_levels(rc_ctx* c, int n_min) {
+  if (n_min < 4) {
+    set_error("multilevel preconditioner: n_min must be at least 4");
+    return RC_ERR_ARG;
+  }
+  if (c->mg_min != n_min) {
+    RC_TRY(sync(c));
+    mg_free(c);
+    c->mg_min = n_min;
+  }
+  if (c->mg_built && c->learn_nmin == n_min) return RC_OK;
+  const int n0 = c->curve.nV;
+  bool ok = c->curve.chain && c->curve.nE == n0 && n0 >= 3;
+  for (int i = 0; ok && i < n0; ++i)
+    ok = c->curve.h_edges[2 * i] == i && c->curve.h_edges[2 * i + 1] == (i + 1) % n0;
+  if (!ok) {
+    set_error("multilevel preconditioner: needs one closed loop with edges (i, i + 1 mod n)");
+    return RC_ERR_UNSUPPORTED;
+  }
+  RC_TRY(mg_build(c));
+  const int nl = (int)c->levels.size();
+  for (int l = 0; l < nl; ++l) {
+    std::vector<Chain> chs = chains_of(level_curve(c, l));
+    bool good = chs.size() == 1 && chs[0].loop;
+    for (int i = 0; good && i < (int)chs[0].verts.size(); ++i) good = chs[0].verts[i] == i;
+    if (!good) {
+      set_error("multilevel preconditioner: a level is not one loop numbered along itself");
+      return RC_ERR_UNSUPPORTED;
+    }
+  }
+  c->learn_off.assign(nl + 1, 0);
+  for (int l = 0; l < nl; ++l) c->learn_off[l + 1] = c->learn_off[l] + level_curve(c, l).nV;
+  const int N = c->learn_off[nl];
+  if (N > c->learn_cap) {
+    RC_TRY(sync(c));
+    learn_free(c);
+    RC_TRY(dalloc(&c->learn_diag, N));
+    RC_TRY(dalloc(&c->learn_scal, N));
+    RC_TRY(dalloc(&c->learn_u, 3 * (size_t)N));
+    RC_TRY(dalloc(&c->learn_w, 3 * (size_t)N));
+    RC_TRY(dalloc(&c->learn_tmp, 3 * (size_t)N));
+    RC_TRY(dalloc(&c->learn_scratch, 10 * (size_t)n0 + 2));
+    RC_TRY(dalloc(&c->learn_X, (size_t)kMlpIn * N));
+    RC_TRY(dalloc(&c->learn_Y, N));
+    RC_TRY(dalloc(&c->learn_dY, N));
+    c->learn_cap = N;
+  }
+  c->learn_N = N;
+  c->learn_nmin = n_min;
+  return RC_OK;
+}
+
+// Level curves, FP64 diagonals, features and (y from the MLP or 1) the
+// scalings at gamma; keep stores the MLP activations for a backward pass.
+rc_status learn_prepare(rc_ctx* c, const double* gamma, int n_min, bool use_mlp, bool keep) {
+  RC_TRY(learn_prepare_levels(c, n_min));
+  if (use_mlp && !c->mlp) {
+    set_error("learned preconditioner: no MLP attached (rc_learned_attach)");
+    return RC_ERR_ARG;
+  }
+  hipStream_t s = c->stream;
+  const int nl = (int)c->levels.size();
+  const double* g = gamma;
+  for (int l = 1; l < nl; ++l) {
+    Level& L = *c->levels[l];
+    hipLaunchKernelGGL(k_gather_coarse, dim3(cdiv(L.curve.nV, 256)), dim3(256), 0, s, g, L.fine_of, L.curve.nV,
+                       L.gamma);
+    g = L.gamma;
+  }
+  RC_HIP(hipMemsetAsync(c->learn_tmp, 0, sizeof(double) * 3 * c->nV, s));
+  for (int l = nl - 1; l >= 0; --l) {  // finest last: its geometry stays loaded
+    const Curve& cv = level_curve(c, l);
+    const double* gl = l == 0 ? gamma : c->levels[l]->gamma;
+    const int o = c->learn_off[l];
+    RC_TRY(launch_geometry(cv, gl, RC_F32, s));
+    RC_TRY(launch_sobolev(cv, c->alpha, c->beta, RC_F64, c->learn_tmp, nullptr, c->learn_diag + o, s));
+    RC_TRY(launch_level_features(cv, gl, c->learn_diag + o, l, nl, c->learn_scratch, c->learn_X + (size_t)kMlpIn * o,
+                                 s));
+  }
+  const int N = c->learn_N;
+  if (use_mlp) RC_TRY(mlp_forward(c->mlp->m, c->learn_X, N, c->learn_Y, keep, s));
+  hipLaunchKernelGGL(k_learn_scal, dim3(cdiv(N, 256)), dim3(256), 0, s, use_mlp ? (const float*)c->learn_Y : nullptr,
+                     (const double*)c->learn_diag, N, c->learn_scal);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+// u_0 = P r and u_l = J_l^T u_{l-1} into learn_u (or, for the backward pass, w).
+static void learn_restrict_all(rc_ctx* c, const double* r, double* u) {
+  hipStream_t s = c->stream;
+  cons_project(c, c->curve, c->cons, r, u);
+  for (int l = 1; l < (int)c->levels.size(); ++l) {
+    const Level& L = *c->levels[l];
+    hipLaunchKernelGGL(k_restrict, dim3(cdiv(L.curve.nV, 256)), dim3(256), 0, s, L.restr_off, L.restr_idx, L.prolong,
+                       L.curve.nV, u + 3 * (size_t)c->learn_off[l - 1], u + 3 * (size_t)c->learn_off[l]);
+  }
+}
+
+// z = P M^-1 P r with the scalings of the last learn_prepare.
+rc_status learn_apply(rc_ctx* c, const double* r, double* z) {
+  hipStream_t s = c->stream;
+  learn_restrict_all(c, r, c->learn_u);
+  const int nl = (int)c->levels.size();
+  for (int l = nl - 1; l >= 0; --l) {
+    const int n = level_curve(c, l).nV, o = c->learn_off[l];
+    const bool coarsest = l == nl - 1;
+    hipLaunchKernelGGL(k_learn_down, dim3(cdiv(n, 256)), dim3(256), 0, s,
+                       coarsest ? (const int2*)nullptr : (const int2*)c->levels[l + 1]->prolong, n,
+                       coarsest ? (const double*)nullptr : (const double*)(c->learn_tmp + 3 * (size_t)c->learn_off[l + 1]),
+                       (const double*)(c->learn_scal + o), (const double*)(c->learn_u + 3 * (size_t)o),
+                       c->learn_tmp + 3 * (size_t)o);
+  }
+  cons_project(c, c->curve, c->cons, c->learn_tmp, z);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+// One training sample (see rc_learned_train_step): with z = P M^-1 P dE,
+// a = <z, g>_A, b = |z|_A^2, q = |g|_A^2, loss = 1 - a^2 / (b q) and
+// d loss / dz = w = P (2 a / (b q)) ((a / b) A z - A g); the derivative with
+// respect to the scaling of vertex v on level l is sum_c (P_l^T w)_v,c (P_l^T P dE)_v,c.
+rc_status learn_train(rc_ctx* c, const double* gamma, const double* dE, const double* g_ref, int n_min, float lr,
+                      double* loss, float* grad_out) {
+  if (!c->mlp) {
+    set_error("learned preconditioner: no MLP attached (rc_learned_attach)");
+    return RC_ERR_ARG;
+  }
+  hipStream_t s = c->stream;
+  const int n3 = 3 * c->nV;
+  RC_TRY(cons_prepare(c, c->curve, c->cons, gamma));
+  RC_TRY(learn_prepare(c, gamma, n_min, true, true));
+  RC_TRY(learn_apply(c, dE, c->z));
+  RC_TRY(launch_sobolev(c->curve, c->alpha, c->beta, RC_F32, c->z, c->q, nullptr, s));       // A z
+  RC_TRY(launch_sobolev(c->curve, c->alpha, c->beta, RC_F32, g_ref, c->tmp, nullptr, s));    // A g
+  double abq[3];
+  vec_dot(c->z, c->tmp, n3, c->red, c->scal, s);
+  vec_dot(c->z, c->q, n3, c->red, c->scal + 1, s);
+  vec_dot(g_ref, c->tmp, n3, c->red, c->scal + 2, s);
+  RC_TRY(fetch(c, c->scal, abq, 3));
+  const double a = abq[0], b = abq[1], q = abq[2];
+  if (!(b > 0) || !(q > 0)) {
+    set_error("learned preconditioner training: zero A-norm (z or g_ref)");
+    return RC_ERR_SINGULAR;
+  }
+  *loss = 1.0 - a * a / (b * q);
+  vec_copy(c->q, c->r, n3, s);
+  vec_axpby(-2.0 * a / (b * q), c->tmp, 2.0 * a * a / (b * b * q), c->r, n3, s);
+  learn_restrict_all(c, c->r, c->learn_w);
+  const int N = c->learn_N;
+  hipLaunchKernelGGL(k_learn_dy, dim3(cdiv(N, 256)), dim3(256), 0, s, (const double*)c->learn_w,
+                     (const double*)c->learn_u, (const double*)c->learn_diag, N, c->learn_dY);
+  Mlp& M = c->mlp->m;
+  RC_TRY(mlp_backward(M, c->learn_X, N, c->learn_dY, M.grad, s));
+  if (grad_out)
+    RC_HIP(hipMemcpyAsync(grad_out, M.grad, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, s));
+  if (lr > 0.f) RC_TRY(mlp_adam(M, M.grad, lr, s));
+  RC_HIP(hipGetLastError());
+  return sync(c);
 }
 
 }  // namespace rc
