@@ -83,11 +83,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--edges", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="step", choices=["step", "bh", "precision", "batch"],
+    ap.add_argument("--workload", default="step", choices=["step", "bh", "precision", "batch", "learned"],
                     help="step: projected Sobolev steps on the 16,384-edge knot (default); "
                          "bh: Barnes-Hut energy+differential on a 262,144-edge knot; "
                          "precision: assembled 16-bit Sobolev block and a solve to 1e-8 on a 32,768-edge knot; "
-                         "batch: 512 packing instances, one captured step")
+                         "batch: 512 packing instances, one captured step; "
+                         "learned: train the learned multilevel preconditioner, then compare PCG preconditioners")
+    ap.add_argument("--train-steps", type=int, default=300, help="Adam steps of the learned preconditioner")
     ap.add_argument("--tune-cache", default=None, help="JSON cache file of the batch tile autotuner")
     ap.add_argument("--fmt", default="bf16", choices=["bf16", "fp16"], help="16-bit format of the precision path")
     args = ap.parse_args()
@@ -102,6 +104,8 @@ def main():
         return bench_precision(args)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "learned":
+        return bench_learned(args)
 
     import numpy as np
     import torch
@@ -504,6 +508,219 @@ def bench_batch(args):
         out["cpu_baseline"]["sample"] += f" (largest instance, {len(ei)} edges)"
     b.close()
     print(json.dumps(out))
+
+
+def bench_learned(args):
+    """Learned multilevel preconditioner: triples (curve, dE, projected gradient) from
+    plain multigrid-PCG flows on knots of 4,096-16,384 edges, Adam training on the
+    GPU, then projected-gradient solves to 1e-6 on held-out knots with Jacobi,
+    multigrid, hand-weighted multilevel and learned multilevel PCG."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2006_07859_amd import (RC_C_BARYCENTER, RC_F32, RC_SOLVE_PCG_JACOBI, RC_SOLVE_PCG_LEARNED,
+                                      RC_SOLVE_PCG_MG, RC_SOLVE_PCG_MULTILEVEL, Context, Mlp, RcError,
+                                      default_ls_opts, default_solve_opts)
+
+    alpha, beta, n_min = 2.0, 4.5, 256
+    MAX_IT_WEAK = 1500
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(0)
+    ctxs = {}
+
+    def context(g, e, key):
+        c = Context(len(g), e, alpha, beta, RC_F32)
+        c.rc_set_constraints(RC_C_BARYCENTER, dev(g))
+        ctxs[key] = c
+        return c
+
+    # data: the initial knot and two flow steps of each training curve
+    mg_tight = default_solve_opts(solver=RC_SOLVE_PCG_MG, tol=1e-7, mg_min_vertices=n_min, op_f64=1, max_iter=600)
+    triples = []
+    t0 = time.perf_counter()
+    train_curves = [(4096, s) for s in (101, 102, 103, 104)] + [(8192, s) for s in (105, 106, 107)] + \
+                   [(16384, s) for s in (108, 109)]
+    for n, seed in train_curves:
+        g, e, _ = gen.fourier_knot(n, seed=seed)
+        c = context(g, e, ("train", n, seed))
+        gamma = dev(g)
+        for k in range(3):
+            E = torch.zeros(1, dtype=torch.float64, device="cuda")
+            dE = torch.zeros(n, 3, dtype=torch.float64, device="cuda")
+            gr = torch.zeros_like(dE)
+            c.rc_differential(gamma, E, dE)
+            try:
+                st = c.rc_sobolev_gradient(gamma, dE, gr, mg_tight)
+                triples.append((c, gamma.clone(), dE, gr))
+                print(f"[bench] learned: triple n {n} seed {seed} step {k}: {st['iterations']} it", file=sys.stderr,
+                      flush=True)
+            except RcError as err:
+                print(f"[bench] learned: n {n} seed {seed} step {k} skipped ({err})", file=sys.stderr, flush=True)
+            if k < 2:
+                c.rc_step(gamma, so=default_solve_opts(solver=RC_SOLVE_PCG_MG, tol=1e-6, mg_min_vertices=n_min),
+                          ls=default_ls_opts())
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    print(f"[bench] learned: {len(triples)} training triples in {t_data:.1f} s", file=sys.stderr, flush=True)
+
+    # training
+    from paper_2006_07859_amd import _lib
+
+    mlp = Mlp(_init_params_host(_lib.mlp_n_params()))
+    for c in {id(t[0]): t[0] for t in triples}.values():
+        c.rc_learned_attach(mlp)
+    losses = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    order = rng.permutation(args.train_steps) % len(triples)
+    for it, k in enumerate(order):
+        c, gamma, dE, gr = triples[k]
+        losses.append(c.rc_learned_train_step(gamma, dE, gr, n_min, 3e-3))
+        if it % 50 == 0:
+            print(f"[bench] learned: train step {it} loss {losses[-1]:.4f}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    # training loss: mean over the first and the last 10% of the steps
+    head = float(np.mean(losses[:max(1, len(losses) // 10)]))
+    tail = float(np.mean(losses[-max(1, len(losses) // 10):]))
+
+    # comparison on held-out knots
+    kinds = {"jacobi": RC_SOLVE_PCG_JACOBI, "multigrid": RC_SOLVE_PCG_MG, "multilevel": RC_SOLVE_PCG_MULTILEVEL,
+             "learned": RC_SOLVE_PCG_LEARNED}
+    results = {}
+    sob_total, sob_launches = 0.0, 0
+    test_losses = {}
+    for n, seed in [(4096, 201), (8192, 202), (16384, 203)]:
+        g, e, _ = gen.fourier_knot(n, seed=seed)
+        c = context(g, e, ("test", n, seed))
+        c.rc_learned_attach(mlp)
+        gamma = dev(g)
+        E = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dE = torch.zeros(n, 3, dtype=torch.float64, device="cuda")
+        c.rc_differential(gamma, E, dE)
+        ref = torch.zeros_like(dE)
+        c.rc_sobolev_gradient(gamma, dE, ref, mg_tight)
+        test_losses[n] = {"learned": c.rc_learned_train_step(gamma, dE, ref, n_min, 0.0)}
+        row = {}
+        for name, kind in kinds.items():
+            out = torch.zeros_like(dE)
+            # the preconditioners alone: no fallback, an iteration cap for the weak ones
+            so = default_solve_opts(solver=kind, tol=1e-6, mg_min_vertices=n_min, op_f64=1,
+                                    max_iter=200 if kind == RC_SOLVE_PCG_MG else MAX_IT_WEAK, fallback_after=0)
+            if kind == RC_SOLVE_PCG_MG:
+                c.rc_sobolev_gradient(gamma, dE, out, so)  # warm-up (allocations, hierarchy)
+            else:
+                c.rc_learned_levels(n_min)  # builds the hierarchy and its buffers
+            torch.cuda.synchronize()
+            c.rc_profile_enable(True)
+            ts = time.perf_counter()
+            st = c.rc_sobolev_gradient(gamma, dE, out, so, check=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - ts
+            ms, nl = c.rc_profile_read(1)
+            c.rc_profile_enable(False)
+            sob_total, sob_launches = sob_total + ms, sob_launches + nl
+            err = (torch.linalg.norm(out - ref) / torch.linalg.norm(ref)).item()
+            row[name] = {"iterations": int(st["iterations"]), "ms": round(dt * 1e3, 2),
+                         "converged": st["status"] == 0, "residual": st["residual"], "rel_error": err}
+            print(f"[bench] learned: n {n} {name}: {row[name]}", file=sys.stderr, flush=True)
+        results[n] = row
+
+    P16 = ordered_disjoint_pairs(gen.fourier_knot(16384, seed=203)[1])
+    learned16 = results[16384]["learned"]
+    # solves/s of the learned preconditioner, 0 when it did not reach the tolerance within the cap
+    value = 1e3 / learned16["ms"] if learned16["converged"] else 0.0
+    sob_avg = sob_total / max(sob_launches, 1) * 1e-3
+    out = {
+        "metric": "projected-gradient solves/s to 1e-6 (learned multilevel PCG, 16,384-edge knot)",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.train_steps,
+        "warmup": 1,
+        "ms_per_step": learned16["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "fourier knots, (alpha,beta)=(2,4.5), barycenter constraint; training triples from "
+                               "plain multigrid-PCG flows on 9 knots of 4,096-16,384 edges; held-out knots of "
+                               "4,096, 8,192 and 16,384 edges solved to a relative FP64 residual of 1e-6",
+                   "edges": 16384, "n_min": n_min},
+        "training": {"triples": len(triples), "data_s": round(t_data, 2), "adam_steps": args.train_steps,
+                     "train_s": round(t_train, 2), "samples_per_s": args.train_steps / t_train,
+                     "loss_first_10pct": head, "loss_last_10pct": tail},
+        "test_loss_learned": {str(k): v["learned"] for k, v in test_losses.items()},
+        "comparison": {str(k): v for k, v in results.items()},
+        "iteration_cap_jacobi_multilevel_learned": MAX_IT_WEAK,
+        "roofline": {"bound": "alu", "achieved": None, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                     "traffic": None, "kernel": "k_sob_pairs (operator products inside PCG, all sizes)",
+                     "launches": sob_launches, "avg_launch_ms": round(sob_avg * 1e3, 4)},
+    }
+    # the roofline of the operator kernel at the largest size, from a dedicated timed run
+    c = ctxs[("test", 16384, 203)]
+    g16 = dev(gen.fourier_knot(16384, seed=203)[0])
+    X = dev(np.random.default_rng(3).normal(size=(16384, 3)))
+    Y = torch.zeros_like(X)
+    c.rc_sobolev_apply(g16, X, Y)
+    c.rc_profile_enable(True)
+    for _ in range(10):
+        c.rc_sobolev_apply(g16, X, Y)
+    ms, nl = c.rc_profile_read(1)
+    c.rc_profile_enable(False)
+    avg = ms / max(nl, 1) * 1e-3
+    ach = FLOPS_PER_PAIR_SOB * P16 / avg / 1e12
+    out["roofline"].update({"achieved": round(ach, 3), "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                            "kernel": "k_sob_pairs<float> (operator product, 16,384 edges)", "launches": nl,
+                            "avg_launch_ms": round(avg * 1e3, 4)})
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_solve(alpha, beta)
+    for c in ctxs.values():
+        c.close()
+    mlp.close()
+    print(json.dumps(out))
+
+
+def _init_params_host(n_params):
+    """Initial MLP parameters: He-scaled hidden layers (seeded), a small output
+    layer and output bias log(e - 1), so that the network starts at y = 1."""
+    import numpy as np
+
+    rng = np.random.default_rng(0)
+    f_in, w = 8, 64
+    W1 = rng.normal(0.0, np.sqrt(2.0 / f_in), size=(f_in, w))
+    W2 = rng.normal(0.0, np.sqrt(2.0 / w), size=(w, w))
+    W3 = rng.normal(0.0, 0.01, size=w)
+    theta = np.concatenate([W1.ravel(), np.zeros(w), W2.ravel(), np.zeros(w), W3, [np.log(np.e - 1.0)]])
+    assert theta.size == n_params
+    return theta
+
+
+def cpu_baseline_solve(alpha, beta, n=1024, seconds=12.0):
+    """The FP64 oracle's projected gradient (dense assembly and saddle solve) on a
+    smaller knot, repeated for a bounded time."""
+    import gen
+    from oracle import constraints as cons
+    from oracle import solve, sobolev, tpe
+
+    from threadpoolctl import threadpool_limits
+
+    g, e, _ = gen.fourier_knot(n, seed=203)
+    x0, _, _ = cons.reference_values(g, e)
+    done, t0 = 0, time.perf_counter()
+    with threadpool_limits(1):  # one BLAS thread, as reported
+        while time.perf_counter() - t0 < seconds:
+            A = sum(sobolev.assemble(g, e, alpha, beta))
+            _, dE = tpe.differential(g, e, alpha, beta)
+            _, C = cons.evaluate(g, e, cons.BARYCENTER, x0)
+            solve.projected_gradient(A, C, dE)
+            done += 1
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} dense FP64 projected-gradient solves (assembly, differential, saddle solve) on a "
+                      f"{n}-edge knot, numpy, one thread"}
 
 
 if __name__ == "__main__":

@@ -94,6 +94,9 @@ typedef struct {
                             FP32 block, refined by the FP64 true residuals (inner_tol) */
   double inner_tol;      /* refinement sweep: restart from the FP64 true residual once the recurrence
                             residual has dropped by this factor (0 = only at tol) */
+  int32_t fallback_after; /* multilevel and learned preconditioners: when > 0, stop after the residual
+                             has grown in this many consecutive iterations, or at max_iter, and solve
+                             again with the multigrid preconditioner (rc_stats.fallback = 1) */
 } rc_solve_opts;
 
 /* Options of the batch step (rc_batch_step). */
@@ -138,6 +141,7 @@ typedef struct {
   double t_eval_ms;      /* rc_step: energy + differential phase (HIP events) */
   double t_solve_ms;     /* rc_step: constraint/multigrid setup + gradient solve */
   double t_search_ms;    /* rc_step: line search with projection */
+  int32_t fallback;      /* 1 when the gradient solve fell back to the multigrid preconditioner */
 } rc_stats;
 
 /* Default option values. */

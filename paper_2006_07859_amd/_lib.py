@@ -50,7 +50,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("solver", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("replace_every", C.c_int32), ("mg_min_vertices", C.c_int32), ("cheb_degree", C.c_int32),
                 ("op_f64", C.c_int32), ("lowp", C.c_int32), ("lowp_band", C.c_int32),
-                ("lowp_min_vertices", C.c_int32), ("lowp_outer", C.c_int32), ("inner_tol", C.c_double)]
+                ("lowp_min_vertices", C.c_int32), ("lowp_outer", C.c_int32), ("inner_tol", C.c_double),
+                ("fallback_after", C.c_int32)]
 
 
 class BatchOpts(C.Structure):
@@ -70,7 +71,7 @@ class Stats(C.Structure):
                 ("residual", C.c_double), ("tau", C.c_double), ("iterations", C.c_int32),
                 ("proj_solve_iterations", C.c_int32), ("backtracks", C.c_int32), ("proj_iters", C.c_int32),
                 ("status", C.c_int32), ("sweeps", C.c_int32), ("t_eval_ms", C.c_double), ("t_solve_ms", C.c_double),
-                ("t_search_ms", C.c_double)]
+                ("t_search_ms", C.c_double), ("fallback", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -273,11 +274,15 @@ class Context:
     def rc_project(self, gamma, X, Y):
         _check(load().rc_project(self.h, self._v(gamma, "gamma"), self._v(X, "X"), self._v(Y, "Y")))
 
-    def rc_sobolev_gradient(self, gamma, dE, g, opts=None):
+    def rc_sobolev_gradient(self, gamma, dE, g, opts=None, check=True):
+        """Returns the solve statistics; check=False returns them (with the status)
+        instead of raising when the solve does not converge."""
         st = Stats()
         o = opts if opts is not None else default_solve_opts()
-        _check(load().rc_sobolev_gradient(self.h, self._v(gamma, "gamma"), self._v(dE, "dE"), self._v(g, "g"),
-                                          C.byref(o), C.byref(st)))
+        status = load().rc_sobolev_gradient(self.h, self._v(gamma, "gamma"), self._v(dE, "dE"), self._v(g, "g"),
+                                            C.byref(o), C.byref(st))
+        if check or status != 5:  # RC_ERR_NOT_CONVERGED
+            _check(status)
         return st.as_dict()
 
     def rc_line_search_step(self, gamma, energy0, dE, g, ls=None, so=None):

@@ -73,6 +73,7 @@ rc_solve_opts resolve(const rc_solve_opts* o) {
   if (d.cheb_degree <= 0) d.cheb_degree = 2;
   if (d.lowp_min_vertices <= 0) d.lowp_min_vertices = 1 << 30;  // finest level only
   if (!(d.inner_tol > 0.0) || !(d.inner_tol < 1.0)) d.inner_tol = 0.0;
+  if (d.fallback_after < 0) d.fallback_after = 0;
   return d;
 }
 
@@ -101,6 +102,7 @@ void rc_default_solve_opts(rc_solve_opts* o) {
   o->lowp_min_vertices = 4096;
   o->lowp_outer = 0;
   o->inner_tol = 0.0;
+  o->fallback_after = 10;
 }
 
 void rc_default_ls_opts(rc_ls_opts* o) {
@@ -307,15 +309,15 @@ rc_status rc_sobolev_gradient(rc_ctx* c, const double* gamma, const double* dE, 
   RC_TRY(no_batch(c, "rc_sobolev_gradient"));
   RC_TRY(check_ptrs({gamma, dE, g}));
   rc_solve_opts o = resolve(opts);
-  RC_TRY(prepare_solver(c, gamma, o));
-  int iters = 0;
+  int iters = 0, fell = 0;
   double res = 0.0;
-  rc_status st = solve_prepared(c, dE, g, o, &iters, &res);
+  rc_status st = solve_gradient(c, gamma, dE, g, o, &iters, &res, &fell);
   if (stats) {
     stats->iterations = iters;
     stats->residual = res;
     stats->sweeps = c->last_sweeps;
     stats->status = st;
+    stats->fallback = fell;
   }
   return st;
 }
@@ -371,14 +373,13 @@ rc_status rc_step(rc_ctx* c, double* gamma, const rc_solve_opts* so, const rc_ls
       st = RC_ERR_NONFINITE;
       break;
     }
-    st = prepare_solver(c, gamma, o);
-    if (st) break;
-    int iters = 0;
+    int iters = 0, fell = 0;
     double res = 0.0;
-    st = solve_prepared(c, dEb, gb, o, &iters, &res);
+    st = solve_gradient(c, gamma, dEb, gb, o, &iters, &res, &fell);  // o becomes multigrid on a fallback
     local.iterations = iters;
     local.residual = res;
     local.sweeps = c->last_sweeps;
+    local.fallback = fell;
     if (st) break;
     vec_dot(gb, gb, 3 * c->nV, c->red, c->scal, s);
     double gg;

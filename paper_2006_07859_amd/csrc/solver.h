@@ -150,6 +150,8 @@ void mg_free(rc_ctx* c);
 
 rc_status load_geometry(rc_ctx* c, const double* gamma);
 rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o);
+rc_status solve_gradient(rc_ctx* c, const double* gamma, const double* rhs, double* out, rc_solve_opts& o,
+                         int* iters, double* res, int* fell);
 rc_status solve_prepared(rc_ctx* c, const double* rhs, double* out, const rc_solve_opts& o, int* iters, double* res);
 
 struct LsResult {

@@ -796,6 +796,8 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
   int it = 0;
   double res = 1.0, res_sweep = 1.0;  // residual at the start of the current sweep
   bool converged = false;
+  const bool watch = o.fallback_after > 0 && (o.solver == RC_SOLVE_PCG_MULTILEVEL || o.solver == RC_SOLVE_PCG_LEARNED);
+  int growing = 0;  // consecutive iterations with a growing recurrence residual
   while (it < o.max_iter && !converged) {
     RC_TRY(precondition(c, o.solver, r, z));
     vec_copy(z, p, n3, s);
@@ -822,8 +824,16 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
       vec_dot(r, r, n3, c->red, c->scal, s);
       double rr;
       RC_TRY(fetch(c, c->scal, &rr, 1));
+      const double res_prev = res;
       res = std::sqrt(rr) / bn;
       if (trace_on()) fprintf(stderr, "[rc pcg] it %d rec-res %.3e\n", it, res);
+      growing = res > res_prev ? growing + 1 : 0;
+      if (watch && growing >= o.fallback_after) {
+        *iters_out = it;
+        *res_out = res;
+        set_error("projected PCG: the residual kept growing");
+        return RC_ERR_NOT_CONVERGED;
+      }
       if (res < std::max(o.tol, o.inner_tol * res_sweep) || (o.replace_every > 0 && since >= o.replace_every)) {
         // FP64 true residual r = P (b - Abar x); restart the recurrence from it
         RC_TRY(apply_A(c, c->curve, x, c->tmp, RC_F64));
@@ -919,6 +929,27 @@ rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o)
     return RC_OK;
   }
   return launch_sobolev(c->curve, c->alpha, c->beta, c->dtype, c->x, c->tmp, c->diag, c->stream);
+}
+
+// Prepare and solve; the multilevel preconditioners fall back to multigrid
+// when their solve diverges or runs out of iterations (o then holds the
+// multigrid options, for the solves that follow at the same curve).
+rc_status solve_gradient(rc_ctx* c, const double* gamma, const double* rhs, double* out, rc_solve_opts& o,
+                         int* iters, double* res, int* fell) {
+  *fell = 0;
+  RC_TRY(prepare_solver(c, gamma, o));
+  rc_status st = solve_prepared(c, rhs, out, o, iters, res);
+  if (st == RC_ERR_NOT_CONVERGED && o.fallback_after > 0 &&
+      (o.solver == RC_SOLVE_PCG_MULTILEVEL || o.solver == RC_SOLVE_PCG_LEARNED)) {
+    if (trace_on()) fprintf(stderr, "[rc pcg] falling back to multigrid after %d iterations\n", *iters);
+    const int spent = *iters;
+    o.solver = RC_SOLVE_PCG_MG;
+    *fell = 1;
+    RC_TRY(prepare_solver(c, gamma, o));
+    st = solve_prepared(c, rhs, out, o, iters, res);
+    *iters += spent;
+  }
+  return st;
 }
 
 rc_status solve_prepared(rc_ctx* c, const double* rhs, double* out, const rc_solve_opts& o, int* iters,

@@ -290,7 +290,9 @@ def test_training_lowers_loss_and_pcg_converges(lib):
         for (g, e, A, C, dE, g_ref), c in zip(probs, ctxs):
             out = zeros(n, 3)
             st = c.rc_sobolev_gradient(dev(g), dev(dE), out,
-                                       default_solve_opts(solver=kind, tol=1e-9, max_iter=2000, mg_min_vertices=n_min))
+                                       default_solve_opts(solver=kind, tol=1e-9, max_iter=2000, mg_min_vertices=n_min,
+                                                          fallback_after=0))
+            assert st["fallback"] == 0
             Ab = np.kron(A, np.eye(3))
             err = host(out).ravel() - g_ref.ravel()
             aerr = np.sqrt(err @ Ab @ err / (g_ref.ravel() @ Ab @ g_ref.ravel()))
@@ -299,6 +301,33 @@ def test_training_lowers_loss_and_pcg_converges(lib):
     for c in ctxs:
         c.close()
     m.close()
+
+
+def test_fallback_to_multigrid(lib):
+    """A multilevel solve that runs out of iterations is redone with multigrid
+    (forced from the host with a small iteration cap)."""
+    from paper_2006_07859_amd import RC_SOLVE_PCG_MULTILEVEL, RcError, default_solve_opts
+
+    n, n_min = 512, 32
+    banner("multilevel PCG falls back to multigrid")
+    g, e = knot(n, 21)
+    A, C, dE, g_ref = gradient_problem(g, e)
+    ctx = context(g, e)
+    out = zeros(n, 3)
+    so = default_solve_opts(solver=RC_SOLVE_PCG_MULTILEVEL, tol=1e-8, max_iter=30, mg_min_vertices=n_min)
+    assert so.fallback_after == 10
+    st = ctx.rc_sobolev_gradient(dev(g), dev(dE), out, so)
+    print(f"  iterations {st['iterations']} fallback {st['fallback']}")
+    assert st["fallback"] == 1 and st["iterations"] > 30 and st["residual"] < 1e-8
+    Ab = np.kron(A, np.eye(3))
+    err = host(out).ravel() - g_ref.ravel()
+    assert np.sqrt(err @ Ab @ err / (g_ref.ravel() @ Ab @ g_ref.ravel())) < 1e-5
+    so.fallback_after = 0
+    with pytest.raises(RcError):
+        ctx.rc_sobolev_gradient(dev(g), dev(dE), out, so)
+    st = ctx.rc_sobolev_gradient(dev(g), dev(dE), out, so, check=False)
+    assert st["status"] == 5 and st["fallback"] == 0 and st["iterations"] == 30
+    ctx.close()
 
 
 def test_rejects_unsupported_curves(lib):
