@@ -5,9 +5,11 @@ Workload (default): a random smooth closed curve with 16,384 edges (Fourier
 modes k = 1..8, coefficients N(0, 1/k^2), seed 0), tangent-point exponents
 (alpha, beta) = (2, 4.5), pair kernels in FP32, barycenter + edge-length
 constraints.  One step is one projected Sobolev step: energy and
-differential, constraint and multigrid setup, projected PCG to a relative
-FP64 residual of 1e-6, and the backtracking line search with constraint
-projection.
+differential, constraint and multigrid setup (BF16 assembled blocks as the
+smoothers' operators), projected PCG to a relative FP64 residual of 1e-6 with
+the FP64 matrix-free operator, and the backtracking line search with
+constraint projection.  The same steps with the plain multigrid (FP32
+matrix-free smoothers) are timed after it for comparison.
 
 Printed (one JSON line): edge-pair evaluations per second of the energy +
 differential phase (ordered disjoint edge pairs / phase time), Sobolev steps
@@ -33,6 +35,8 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_PAIR_TPE = 344   # energy + differential, 86 per vertex pair, 2 transcendentals
 FLOPS_PER_PAIR_SOB = 198   # operator A = B + B0 applied to 3 right-hand sides
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed); the non-packed issue limit is half
+PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 
 
 def ordered_disjoint_pairs(edges):
@@ -123,7 +127,10 @@ def main():
     ctx = Context(len(g), e, alpha, beta, RC_F32)
     gamma = dev(g)
     ctx.rc_set_constraints(RC_C_BARYCENTER | RC_C_EDGE_LENGTH, gamma)
-    so = default_solve_opts(solver=RC_SOLVE_PCG_MG, tol=1e-6, mg_min_vertices=256, cheb_degree=2, op_f64=1)
+    # multigrid PCG with the FP64 matrix-free Krylov operator (the residual's judge) and BF16 assembled
+    # blocks as the smoothers' operators on every level with >= 512 vertices
+    so = default_solve_opts(solver=RC_SOLVE_PCG_MG, tol=1e-6, mg_min_vertices=256, cheb_degree=2, op_f64=1,
+                            lowp=1, lowp_band=16, lowp_min_vertices=512)
     ls = default_ls_opts()
 
     for _ in range(args.warmup):
@@ -143,32 +150,36 @@ def main():
     T = time.perf_counter() - t0
     tpe_ms, tpe_n = ctx.rc_profile_read(0)
     sob_ms, sob_n = ctx.rc_profile_read(1)
+    lp_ms, lp_n = ctx.rc_profile_read(2)
+    s64_ms, s64_n = ctx.rc_profile_read(4)
     ctx.rc_profile_enable(False)
 
     t_eval = float(np.mean([s["t_eval_ms"] for s in stats])) * 1e-3
     value = P / t_eval
     tpe_avg = tpe_ms / max(tpe_n, 1) * 1e-3
-    sob_avg = sob_ms / max(sob_n, 1) * 1e-3
     roof_tpe = FLOPS_PER_PAIR_TPE * P / tpe_avg / 1e12
-    roof_sob = FLOPS_PER_PAIR_SOB * P / sob_avg / 1e12
-    # the dominant kernel of the step is the one with the larger total time
-    if sob_ms >= tpe_ms:
-        dom = {"kernel": "k_sob_pairs<float> (operator, finest level)", "launches": sob_n,
-               "avg_ms": sob_avg * 1e3, "flops_per_pair": FLOPS_PER_PAIR_SOB, "achieved_tflops": roof_sob}
-    else:
-        dom = {"kernel": "k_tpe_pairs<float> (energy+differential)", "launches": tpe_n,
-               "avg_ms": tpe_avg * 1e3, "flops_per_pair": FLOPS_PER_PAIR_TPE, "achieved_tflops": roof_tpe}
-    roofline = {
-        "bound": "alu",
-        "achieved": round(dom["achieved_tflops"], 3),
-        "peak": PEAK_FP32_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(dom["achieved_tflops"] / PEAK_FP32_TFLOPS, 4),
-        "traffic": None,
-        "kernel": dom["kernel"],
-        "avg_launch_ms": round(dom["avg_ms"], 4),
-        "launches": dom["launches"],
-    }
+    # the timed kernels of the step (finest level), each against its own roofline
+    kernels = [
+        ("k_tpe_pairs<float> (energy+differential)", tpe_ms, tpe_n, FLOPS_PER_PAIR_TPE * P / 1e12, "alu",
+         PEAK_FP32_TFLOPS, "TFLOP/s"),
+        ("k_sob_pairs<float> (FP32 operator, finest level)", sob_ms, sob_n, FLOPS_PER_PAIR_SOB * P / 1e12, "alu",
+         PEAK_FP32_TFLOPS, "TFLOP/s"),
+        ("k_sob_pairs<double> (FP64 Krylov operator, finest level)", s64_ms, s64_n, FLOPS_PER_PAIR_SOB * P / 1e12,
+         "alu", PEAK_FP64_TFLOPS, "TFLOP/s"),
+        ("k_lowp_gemv<bf16> (smoother product, finest level)", lp_ms, lp_n, n * n * 2 / 1e9, "hbm", PEAK_HBM_GBS,
+         "GB/s"),
+    ]
+    rooflines = []
+    for name, ms, nl, work, bound, peak, unit in kernels:
+        if nl == 0:
+            continue
+        avg = ms / nl * 1e-3
+        ach = work / avg
+        rooflines.append({"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+                          "frac": round(ach / peak, 4), "traffic": None, "kernel": name,
+                          "avg_launch_ms": round(avg * 1e3, 4), "launches": nl, "total_ms": round(ms, 2)})
+    # the dominant kernel of the step: the largest total time among the timed ones
+    roofline = max(rooflines, key=lambda r: r["total_ms"])
     out = {
         "metric": "edge-pair evals/s (energy+grad)",
         "value": value,
@@ -184,7 +195,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"fourier knot, {n} edges, (alpha,beta)=(2,4.5), FP32 pair kernels, barycenter+edge-length "
-                        f"constraints, multigrid PCG to 1e-6 FP64 residual, backtracking line search",
+                        f"constraints, multigrid PCG to 1e-6 FP64 residual (FP64 matrix-free Krylov operator, "
+                        f"BF16 assembled smoother blocks), backtracking line search",
             "edges": n,
             "ordered_pairs": P,
         },
@@ -198,12 +210,29 @@ def main():
         "pcg_residual": [s["residual"] for s in stats],
         "projection_solve_iterations": [s["proj_solve_iterations"] for s in stats],
         "roofline": roofline,
+        "rooflines_timed_kernels": rooflines,
         "roofline_energy_differential": {
             "kernel": "k_tpe_pairs<float>", "launches": tpe_n, "avg_launch_ms": round(tpe_avg * 1e3, 4),
             "achieved": round(roof_tpe, 3), "unit": "TFLOP/s", "frac": round(roof_tpe / PEAK_FP32_TFLOPS, 4),
             "pairs_per_s_kernel": P / tpe_avg,
         },
     }
+    # the same steps with the plain solver (FP32 matrix-free smoothers), from the same start
+    ctx.close()
+    ctx = Context(len(g), e, alpha, beta, RC_F32)
+    gamma = dev(g)
+    ctx.rc_set_constraints(RC_C_BARYCENTER | RC_C_EDGE_LENGTH, gamma)
+    plain = default_solve_opts(solver=RC_SOLVE_PCG_MG, tol=1e-6, mg_min_vertices=256, cheb_degree=2, op_f64=1)
+    ctx.rc_step(gamma, so=plain, ls=ls)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    pst = [ctx.rc_step(gamma, so=plain, ls=ls) for _ in range(2)]
+    torch.cuda.synchronize()
+    Tp = (time.perf_counter() - tp) / 2
+    out["plain_multigrid"] = {"sobolev_steps_per_s": 1.0 / Tp, "ms_per_step": Tp * 1e3,
+                              "pcg_iterations": [s["iterations"] for s in pst],
+                              "smoothers": "FP32 matrix-free operator on every level"}
+    out["speedup_vs_plain"] = (args.steps / T) / (1.0 / Tp)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, e, alpha, beta)
     ctx.close()

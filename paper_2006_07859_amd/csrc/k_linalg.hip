@@ -265,8 +265,10 @@ void dense_gemv(const double* A, const double* x, double* y, int n, hipStream_t 
 // runs in one thread once per system; it stores l and 1/u.  A solve is two
 // first-order linear recurrences, forward  z[k] = b[k] - l[k] z[k-1]  and
 // backward  y[k] = (z[k] - c[k] y[k+1]) / u[k].  Each is an affine map per row;
-// one workgroup composes the maps of contiguous chunks per thread, scans the
-// chunk composites across the workgroup in LDS, and then replays its chunk.
+// one workgroup composes the maps of contiguous chunks per thread (held in
+// registers up to 16 rows per thread), scans the chunk composites across the
+// workgroup (wave shuffles, then one LDS exchange of the 16 wave totals), and
+// then replays its chunk.
 // The system is symmetric positive definite (a constraint Gram matrix), so
 // the factorisation needs no pivoting.
 __global__ void k_tridiag_factor(const double* __restrict__ a, const double* __restrict__ d,
@@ -288,78 +290,149 @@ __global__ void k_tridiag_factor(const double* __restrict__ a, const double* __r
 }
 
 constexpr int kTriThreads = 1024;
+constexpr int kTriWaves = kTriThreads / 64;
+constexpr int kTriReg = 16;  // rows per thread held in registers (n <= 16,384); longer chunks reload
+
+// Composite affine maps: (a, b) is v -> a v + b.  scan_compose returns, for
+// every thread, the composite of all maps of the threads before it (in scan
+// order: increasing t, or decreasing t when `rev`), i.e. the map from the
+// value entering the recurrence to the value entering this thread's chunk.
+// Within a wave: shuffles; across waves: one LDS exchange (2 barriers).
+__device__ __forceinline__ void scan_compose(double& a, double& b, bool rev, double* wa, double* wb) {
+  const int t = threadIdx.x, lane = t % 64, w = t / 64;
+  // inclusive scan inside the wave, in scan order (lane order reversed for rev)
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double pa = rev ? __shfl_down(a, off, 64) : __shfl_up(a, off, 64);
+    const double pb = rev ? __shfl_down(b, off, 64) : __shfl_up(b, off, 64);
+    const bool has = rev ? lane + off < 64 : lane >= off;
+    if (has) {  // earlier composite (pa, pb) first, then this one
+      b = a * pb + b;
+      a = a * pa;
+    }
+  }
+  // wave totals: the last lane in scan order holds its wave's composite
+  const int last = rev ? 0 : 63;
+  if (lane == last) {
+    wa[w] = a;
+    wb[w] = b;
+  }
+  // exclusive value inside the wave: the inclusive value of the previous lane in scan order
+  double ea = rev ? __shfl_down(a, 1, 64) : __shfl_up(a, 1, 64);
+  double eb = rev ? __shfl_down(b, 1, 64) : __shfl_up(b, 1, 64);
+  const bool first = rev ? lane == 63 : lane == 0;
+  if (first) {
+    ea = 1.0;
+    eb = 0.0;
+  }
+  __syncthreads();
+  if (t == 0) {  // exclusive scan of the wave totals in scan order, in place
+    double ca = 1.0, cb = 0.0;
+    for (int k = 0; k < kTriWaves; ++k) {
+      const int ww = rev ? kTriWaves - 1 - k : k;
+      const double ta = wa[ww], tb = wb[ww];
+      wa[ww] = ca;
+      wb[ww] = cb;
+      cb = ta * cb + tb;
+      ca = ta * ca;
+    }
+  }
+  __syncthreads();
+  // prefix of this thread = (waves before) then (lanes before in this wave)
+  const double pa = wa[w], pb = wb[w];
+  a = ea * pa;
+  b = ea * pb + eb;
+}
 
 __global__ __launch_bounds__(kTriThreads) void k_tridiag_solve(const double* __restrict__ lo,
                                                                 const double* __restrict__ uinv,
                                                                 const double* __restrict__ c,
                                                                 const double* __restrict__ b, double* __restrict__ y,
                                                                 int n) {
-  __shared__ double sA[kTriThreads], sB[kTriThreads];
+  __shared__ double wa[kTriWaves], wb[kTriWaves];
   const int t = threadIdx.x;
   const int m = (n + kTriThreads - 1) / kTriThreads;
-  const int k0 = min(n, t * m), k1 = min(n, k0 + m);
+  const int k0 = min(n, t * m), k1 = min(n, k0 + m), cnt = k1 - k0;
+  const bool reg = m <= kTriReg;
+  double rl[kTriReg], rz[kTriReg];
   // forward: z[k] = -l[k] z[k-1] + b[k]; chunk composite z_out = A z_in + B
   double A = 1.0, B = 0.0;
-  for (int k = k0; k < k1; ++k) {
-    const double l = lo[k];
-    A = -l * A;
-    B = -l * B + b[k];
-  }
-  sA[t] = A;
-  sB[t] = B;
-  __syncthreads();
-  // inclusive scan of composites (later chunk applied after earlier ones)
-  for (int off = 1; off < kTriThreads; off <<= 1) {
-    double pa = 1.0, pb = 0.0;
-    if (t >= off) {
-      pa = sA[t - off];
-      pb = sB[t - off];
+  if (reg) {
+#pragma unroll
+    for (int j = 0; j < kTriReg; ++j) {
+      rl[j] = j < cnt ? lo[k0 + j] : 0.0;
+      rz[j] = j < cnt ? b[k0 + j] : 0.0;
     }
-    __syncthreads();
-    if (t >= off) {
-      const double ca = sA[t], cb = sB[t];
-      sA[t] = ca * pa;
-      sB[t] = ca * pb + cb;
+#pragma unroll
+    for (int j = 0; j < kTriReg; ++j)
+      if (j < cnt) {
+        A = -rl[j] * A;
+        B = -rl[j] * B + rz[j];
+      }
+  } else {
+    for (int k = k0; k < k1; ++k) {
+      const double l = lo[k];
+      A = -l * A;
+      B = -l * B + b[k];
     }
-    __syncthreads();
   }
-  double zin = (t > 0) ? sB[t - 1] : 0.0;  // z before the chunk (z[-1] = 0)
-  __syncthreads();
-  for (int k = k0; k < k1; ++k) {
-    zin = -lo[k] * zin + b[k];
-    y[k] = zin;
+  scan_compose(A, B, false, wa, wb);
+  double zin = B;  // z before the chunk (z[-1] = 0)
+  if (reg) {
+#pragma unroll
+    for (int j = 0; j < kTriReg; ++j)
+      if (j < cnt) {
+        zin = -rl[j] * zin + rz[j];
+        rz[j] = zin;
+      }
+  } else {
+    for (int k = k0; k < k1; ++k) {
+      zin = -lo[k] * zin + b[k];
+      y[k] = zin;
+    }
   }
-  __syncthreads();
+  __syncthreads();  // the LDS slots are reused by the second scan
   // backward: y[k] = -c[k] uinv[k] y[k+1] + z[k] uinv[k], scanned from the end
   A = 1.0;
   B = 0.0;
-  for (int k = k1 - 1; k >= k0; --k) {
-    const double ui = uinv[k];
-    A = -c[k] * ui * A;
-    B = -c[k] * ui * B + y[k] * ui;
-  }
-  sA[t] = A;
-  sB[t] = B;
-  __syncthreads();
-  for (int off = 1; off < kTriThreads; off <<= 1) {
-    double pa = 1.0, pb = 0.0;
-    if (t + off < kTriThreads) {
-      pa = sA[t + off];
-      pb = sB[t + off];
+  if (reg) {
+    // rl <- -c/u (the coupling), rz <- z/u (the offset)
+#pragma unroll
+    for (int j = 0; j < kTriReg; ++j) {
+      const double ui = j < cnt ? uinv[k0 + j] : 0.0;
+      rl[j] = j < cnt ? -c[k0 + j] * ui : 0.0;
+      rz[j] *= ui;
     }
-    __syncthreads();
-    if (t + off < kTriThreads) {
-      const double ca = sA[t], cb = sB[t];
-      sA[t] = ca * pa;
-      sB[t] = ca * pb + cb;
+#pragma unroll
+    for (int j = kTriReg - 1; j >= 0; --j)
+      if (j < cnt) {
+        A = rl[j] * A;
+        B = rl[j] * B + rz[j];
+      }
+    scan_compose(A, B, true, wa, wb);
+    double yin = B;  // y after the chunk (y[n] = 0)
+#pragma unroll
+    for (int j = kTriReg - 1; j >= 0; --j)
+      if (j < cnt) {
+        yin = rl[j] * yin + rz[j];
+        rz[j] = yin;
+      }
+#pragma unroll
+    for (int j = 0; j < kTriReg; ++j)
+      if (j < cnt) y[k0 + j] = rz[j];
+  } else {
+    for (int k = k1 - 1; k >= k0; --k) {
+      const double ui = uinv[k];
+      A = -c[k] * ui * A;
+      B = -c[k] * ui * B + y[k] * ui;
     }
-    __syncthreads();
-  }
-  double yin = (t + 1 < kTriThreads) ? sB[t + 1] : 0.0;  // y after the chunk (y[n] = 0)
-  for (int k = k1 - 1; k >= k0; --k) {
-    const double ui = uinv[k];
-    yin = -c[k] * ui * yin + y[k] * ui;
-    y[k] = yin;
+    scan_compose(A, B, true, wa, wb);
+    double yin = B;
+    for (int k = k1 - 1; k >= k0; --k) {
+      const double ui = uinv[k];
+      yin = -c[k] * ui * yin + y[k] * ui;
+      y[k] = yin;
+    }
   }
 }
 

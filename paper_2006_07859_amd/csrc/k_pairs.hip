@@ -872,9 +872,10 @@ rc_status launch_tpe(const Curve& c, double alpha, double beta, rc_dtype prec, b
 template <typename R, int EC>
 static void run_sob(const Curve& c, const EdgeGeom<R>& g, V4<R>* const* rhs, double half_expo, hipStream_t s) {
   dim3 grid(cdiv(c.nE, kTile), c.nchunk);
-  const bool timed = std::is_same<R, float>::value && c.timer && c.timer->on;
+  const bool timed = c.timer && c.timer->on;
+  std::vector<hipEvent_t>* tv = timed ? (std::is_same<R, float>::value ? &c.timer->sob : &c.timer->sob64) : nullptr;
   if (c.n_inst > 0) hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, c.counter);
-  if (timed) c.timer->mark(c.timer->sob, s);
+  if (timed) c.timer->mark(*tv, s);
   if (c.n_inst > 0)
     hipLaunchKernelGGL((k_sob_items<R, EC>), dim3(c.persist_blocks), dim3(kTile), 0, s, g.a, g.b, g.t, c.edges,
                        rhs[0], rhs[1], c.nE, c.items, c.n_items, c.counter, c.inst_of_edge, c.inst_mask,
@@ -882,7 +883,7 @@ static void run_sob(const Curve& c, const EdgeGeom<R>& g, V4<R>* const* rhs, dou
   else
     hipLaunchKernelGGL((k_sob_pairs<R, EC>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, rhs[0], rhs[1],
                        c.nE, c.src_per_chunk, R(half_expo), c.part);
-  if (timed) c.timer->mark(c.timer->sob, s);
+  if (timed) c.timer->mark(*tv, s);
 }
 
 template <typename R>

@@ -835,8 +835,9 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
         return RC_ERR_NOT_CONVERGED;
       }
       if (res < std::max(o.tol, o.inner_tol * res_sweep) || (o.replace_every > 0 && since >= o.replace_every)) {
-        // FP64 true residual r = P (b - Abar x); restart the recurrence from it
-        RC_TRY(apply_A(c, c->curve, x, c->tmp, RC_F64));
+        // true residual r = P (b - Abar x) (FP64); restart the recurrence from it
+        // a loose solve (tol >= 1e-4) checks in its own operator's precision
+        RC_TRY(apply_A(c, c->curve, x, c->tmp, o.tol >= 1e-4 ? op : RC_F64));
         vec_copy(b, r, n3, s);
         vec_axpby(-1.0, c->tmp, 1.0, r, n3, s);
         cons_project(c, c->curve, c->cons, r, r);
@@ -977,7 +978,7 @@ static rc_status projection_increment(rc_ctx* c, const double* phi, double* x, c
   }
   hipLaunchKernelGGL(k_negate, dim3(cdiv(k, 256)), dim3(256), 0, s, phi, c->phi + k, k);
   cons_min_norm(c, c->phi + k, c->zmin);
-  RC_TRY(apply_A(c, c->curve, c->zmin, c->inc, RC_F64));
+  RC_TRY(apply_A(c, c->curve, c->zmin, c->inc, o.op_f64 ? RC_F64 : c->dtype));
   double res = 0.0;
   rc_status st = pcg_solve(c, c->inc, c->x, o, iters, &res);
   if (st != RC_OK && st != RC_ERR_NOT_CONVERGED) return st;
@@ -1035,7 +1036,12 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
       int pit = 0;
       RC_TRY(load_geometry(c, gamma));
       rc_solve_opts po = so;
-      if (ls.proj_solve_tol > 0) po.tol = ls.proj_solve_tol;
+      if (ls.proj_solve_tol > 0) {
+        // a loose increment solve: its operator runs in the context's precision
+        // (C x = -Phi holds whatever the solve's accuracy)
+        po.tol = ls.proj_solve_tol;
+        if (ls.proj_solve_tol >= 1e-4) po.op_f64 = 0;
+      }
       RC_TRY(projection_increment(c, c->phi, c->dx, po, &pit));
       out->proj_solve_iters += pit;
       vec_axpby(1.0, c->dx, 1.0, c->trial, n3, s);

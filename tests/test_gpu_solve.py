@@ -150,3 +150,40 @@ def test_step_multigrid_edge_lengths(lib):
     phi, _ = cons.evaluate(new, e, BARY | EDGE, *refs, jacobian=False)
     ell, _, _ = tpe.edge_geometry(g, e)
     assert np.abs(phi[3:]).max() < 1e-8 * ell.mean()
+
+
+@pytest.mark.parametrize("n", [3000, 16384, 40000])
+def test_projector_long_loops(lib, n):
+    """Edge-length + barycenter projector on long loops: every chunk length of
+    the tridiagonal solve (registers up to 16 rows per thread, reloads beyond).
+    Against the oracle's dense projector at 3,000 edges; by its defining
+    properties (C P x = 0, P P x = P x, symmetry) at every size."""
+    from paper_2006_07859_amd import RC_F64
+
+    banner(f"projector with edge-length rows, n={n}")
+    g, e, _ = gen.fourier_knot(n, seed=4)
+    ctx = make(lib, g, e, 2.0, 4.5, RC_F64, BARY | EDGE)
+    gp = g + 1e-3 * np.random.default_rng(2).normal(size=g.shape) * np.linalg.norm(g[1] - g[0])
+    rng = np.random.default_rng(3)
+    X, Z = rng.normal(size=g.shape), rng.normal(size=g.shape)
+    PX, PZ, PPX = zeros(n, 3), zeros(n, 3), zeros(n, 3)
+    ctx.rc_project(dev(gp), dev(X), PX)
+    ctx.rc_project(dev(gp), dev(Z), PZ)
+    ctx.rc_project(dev(gp), PX, PPX)
+    px, pz = host(PX), host(PZ)
+    assert relnorm(host(PPX), px) < 1e-12
+    assert (X * pz).sum() == pytest.approx((Z * px).sum(), rel=1e-11)
+    # C y for the edge rows (T_I . (y_i2 - y_i1)) and the barycenter rows
+    x0, _, _ = cons.reference_values(g, e)
+    ell, T, xm = tpe.edge_geometry(gp, e)
+    i1, i2 = e[:, 0], e[:, 1]
+    edge_rows = (T * (px[i2] - px[i1])).sum(1)
+    assert np.abs(edge_rows).max() < 1e-11 * np.abs(px).max()
+    bary = (0.5 * ell[:, None] * (px[i1] + px[i2]) + (xm - x0) * edge_rows[:, None]).sum(0)
+    assert np.abs(bary).max() < 1e-10 * ell.sum() * np.abs(px).max()
+    if n <= 3000:
+        _, C = cons.evaluate(gp, e, BARY | EDGE, *cons.reference_values(g, e))
+        x = X.ravel()
+        ref = x - C.T @ np.linalg.solve(C @ C.T, C @ x)
+        assert relnorm(px.ravel(), ref) < 1e-11
+    ctx.close()
