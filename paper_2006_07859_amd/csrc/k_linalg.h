@@ -38,6 +38,15 @@ void cons_apply_CT(const double* geo, const int* inc_off, const int* inc, const 
 void cons_border_solve(const double* Sinv, const double* wb, const double* dots, double* rhs, int nb, double* yb,
                        hipStream_t s);
 void cons_sub_Zy(const double* Z, const double* yb, int nb, int np, double* yp, hipStream_t s);
+// P x in three launches when nb <= kProjMaxBorder (in and out may alias:
+// every output entry is written by the last launch from its own input
+// entry).  part: device double [64 * 2 * kProjMaxBorder]; wp, yp: [np]; yb: [nb].
+constexpr int kProjMaxBorder = 8;
+void cons_project_fused(const double* geo, const int2* edges, const int* path_edge, int np, const double* rows,
+                        int nb, const double* Z, const double* Sinv, const double* lo, const double* uinv,
+                        const double* tc, const int* inc_off, const int* inc, const int* edge_path_row, int nV,
+                        const double* in, double* out, double* part, double* wp, double* yp, double* yb,
+                        hipStream_t s);
 
 // dense direct path
 void dense_build_H(const double* A, const double* CtC, int nV, double* H, hipStream_t s);

@@ -344,12 +344,11 @@ __device__ __forceinline__ void scan_compose(double& a, double& b, bool rev, dou
   b = ea * pb + eb;
 }
 
-__global__ __launch_bounds__(kTriThreads) void k_tridiag_solve(const double* __restrict__ lo,
-                                                                const double* __restrict__ uinv,
-                                                                const double* __restrict__ c,
-                                                                const double* __restrict__ b, double* __restrict__ y,
-                                                                int n) {
-  __shared__ double wa[kTriWaves], wb[kTriWaves];
+// y = K^-1 b for the factorised tridiagonal K, by one workgroup of
+// kTriThreads threads (every thread must call it); wa, wb: LDS [kTriWaves].
+__device__ __forceinline__ void tridiag_solve_wg(const double* __restrict__ lo, const double* __restrict__ uinv,
+                                                 const double* __restrict__ c, const double* __restrict__ b,
+                                                 double* __restrict__ y, int n, double* wa, double* wb) {
   const int t = threadIdx.x;
   const int m = (n + kTriThreads - 1) / kTriThreads;
   const int k0 = min(n, t * m), k1 = min(n, k0 + m), cnt = k1 - k0;
@@ -434,6 +433,15 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag_solve(const double* __r
       y[k] = yin;
     }
   }
+}
+
+__global__ __launch_bounds__(kTriThreads) void k_tridiag_solve(const double* __restrict__ lo,
+                                                                const double* __restrict__ uinv,
+                                                                const double* __restrict__ c,
+                                                                const double* __restrict__ b, double* __restrict__ y,
+                                                                int n) {
+  __shared__ double wa[kTriWaves], wb[kTriWaves];
+  tridiag_solve_wg(lo, uinv, c, b, y, n, wa, wb);
 }
 
 void tridiag_factor(const double* a, const double* d, const double* c, int n, double* lo, double* uinv, int* info,
@@ -682,6 +690,140 @@ void cons_border_solve(const double* Sinv, const double* wb, const double* dots,
 void cons_sub_Zy(const double* Z, const double* yb, int nb, int np, double* yp, hipStream_t s) {
   if (np <= 0) return;
   hipLaunchKernelGGL(k_sub_Zy, dim3(cdiv(np, 256)), dim3(256), 0, s, Z, yb, nb, np, yp);
+}
+
+// ---------------------------------------------------------------------------
+// the projector P x = x - C^T (C C^T)^-1 C x in three launches (nb <= 8)
+// ---------------------------------------------------------------------------
+// With K = C C^T split into the path block Kpp (tridiagonal), the border
+// block Kbb and their coupling Kpb, and Z = Kpp^-1 Kpb (columns), the Schur
+// complement solve of K y = (wp, wb) is
+//   yb = S^-1 (wb - Z^T wp),  yp = Kpp^-1 wp - Z yb,   S = Kbb - Kpb^T Z,
+// using Kpb^T Kpp^-1 = Z^T (Kpp is symmetric).
+//   1. k_proj_rows: wp = C_path x, and per-workgroup partial sums of the
+//      border rows' dot products wb = rows . x and of Z^T wp;
+//   2. k_proj_solve (one workgroup): the partial sums, yb, and Kpp^-1 wp;
+//   3. k_apply_CT_z: out = x - C^T y with yp corrected by -Z yb per row.
+constexpr int kProjBlocks = 64, kProjSlots = 2 * kProjMaxBorder;
+
+__global__ __launch_bounds__(256) void k_proj_rows(const double* __restrict__ geo, const int2* __restrict__ edges,
+                                                   const int* __restrict__ path_edge, int np,
+                                                   const double* __restrict__ rows, int nb,
+                                                   const double* __restrict__ Z, int nV, const double* __restrict__ x,
+                                                   double* __restrict__ wp, double* __restrict__ part) {
+  double acc[kProjSlots];
+#pragma unroll
+  for (int q = 0; q < kProjSlots; ++q) acc[q] = 0.0;
+  const int nmax = max(np, nV);
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nmax; i += gridDim.x * 256) {
+    if (i < np) {
+      const int I = path_edge[i];
+      const int2 e = edges[I];
+      const double* g = geo + 8 * (size_t)I;
+      const double w = g[1] * (x[3 * e.x] - x[3 * e.y]) + g[2] * (x[3 * e.x + 1] - x[3 * e.y + 1]) +
+                       g[3] * (x[3 * e.x + 2] - x[3 * e.y + 2]);
+      wp[i] = w;
+#pragma unroll
+      for (int r = 0; r < kProjMaxBorder; ++r)
+        if (r < nb) acc[kProjMaxBorder + r] += Z[(size_t)r * np + i] * w;
+    }
+    if (i < nV) {
+#pragma unroll
+      for (int r = 0; r < kProjMaxBorder; ++r)
+        if (r < nb) {
+          const double* rv = rows + ((size_t)r * nV + i) * 3;
+          acc[r] += rv[0] * x[3 * i] + rv[1] * x[3 * i + 1] + rv[2] * x[3 * i + 2];
+        }
+    }
+  }
+  __shared__ double sred[4][kProjSlots];
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+#pragma unroll
+  for (int q = 0; q < kProjSlots; ++q) {
+    double v = acc[q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) sred[w][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kProjSlots) {
+    const int q = threadIdx.x;
+    part[(size_t)blockIdx.x * kProjSlots + q] = ((sred[0][q] + sred[1][q]) + sred[2][q]) + sred[3][q];
+  }
+}
+
+__global__ __launch_bounds__(kTriThreads) void k_proj_solve(const double* __restrict__ part, int nblk, int nb,
+                                                           const double* __restrict__ Sinv,
+                                                           const double* __restrict__ lo,
+                                                           const double* __restrict__ uinv,
+                                                           const double* __restrict__ tc,
+                                                           const double* __restrict__ wp, double* __restrict__ yp,
+                                                           double* __restrict__ yb, int np) {
+  __shared__ double wa[kTriWaves], wbs[kTriWaves];
+  __shared__ double sp[kProjBlocks][kProjSlots + 1];
+  __shared__ double tot[kProjSlots];
+  const int t = threadIdx.x;
+  const int q = t % kProjSlots, blk = t / kProjSlots;  // 1024 threads = 64 blocks x 16 slots
+  sp[blk][q] = blk < nblk ? part[(size_t)blk * kProjSlots + q] : 0.0;
+  __syncthreads();
+  if (t < kProjSlots) {
+    double v = 0.0;
+    for (int k = 0; k < kProjBlocks; ++k) v += sp[k][t];
+    tot[t] = v;
+  }
+  __syncthreads();
+  if (t < nb) {  // yb = S^-1 (wb - Z^T wp)
+    double v = 0.0;
+    for (int j = 0; j < nb; ++j) v += Sinv[t * nb + j] * (tot[j] - tot[kProjMaxBorder + j]);
+    yb[t] = v;
+  }
+  if (np > 0) tridiag_solve_wg(lo, uinv, tc, wp, yp, np, wa, wbs);
+}
+
+// out_v = in_v - [ sum_{path rows k at v} s(v) T_I (yp_k - (Z yb)_k) + sum_r yb[r] rows[r][v] ]
+__global__ __launch_bounds__(256) void k_apply_CT_z(const double* __restrict__ geo, const int* __restrict__ inc_off,
+                                                    const int* __restrict__ inc,
+                                                    const int* __restrict__ edge_path_row,
+                                                    const double* __restrict__ yp, const double* __restrict__ Z,
+                                                    int np, const double* __restrict__ rows,
+                                                    const double* __restrict__ yb, int nb, int nV,
+                                                    const double* __restrict__ in, double* __restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nV) return;
+  double ybr[kProjMaxBorder];
+#pragma unroll
+  for (int r = 0; r < kProjMaxBorder; ++r) ybr[r] = r < nb ? yb[r] : 0.0;
+  double acc[3] = {0, 0, 0};
+  for (int k = inc_off[v]; k < inc_off[v + 1]; ++k) {
+    const int I = inc[k] >> 1;
+    const int pr = edge_path_row[I];
+    if (pr < 0) continue;
+    double y = yp[pr];
+#pragma unroll
+    for (int r = 0; r < kProjMaxBorder; ++r)
+      if (r < nb) y -= Z[(size_t)r * np + pr] * ybr[r];
+    const double sg = (inc[k] & 1) ? -1.0 : 1.0;
+    const double* g = geo + 8 * (size_t)I;
+    for (int cc = 0; cc < 3; ++cc) acc[cc] += sg * g[1 + cc] * y;
+  }
+#pragma unroll
+  for (int r = 0; r < kProjMaxBorder; ++r)
+    if (r < nb)
+      for (int cc = 0; cc < 3; ++cc) acc[cc] += ybr[r] * rows[((size_t)r * nV + v) * 3 + cc];
+  for (int cc = 0; cc < 3; ++cc) out[3 * v + cc] = in[3 * v + cc] - acc[cc];
+}
+
+void cons_project_fused(const double* geo, const int2* edges, const int* path_edge, int np, const double* rows,
+                        int nb, const double* Z, const double* Sinv, const double* lo, const double* uinv,
+                        const double* tc, const int* inc_off, const int* inc, const int* edge_path_row, int nV,
+                        const double* in, double* out, double* part, double* wp, double* yp, double* yb,
+                        hipStream_t s) {
+  const int nblk = std::min(kProjBlocks, std::max(1, cdiv(std::max(np, nV), 256)));
+  hipLaunchKernelGGL(k_proj_rows, dim3(nblk), dim3(256), 0, s, geo, edges, path_edge, np, rows, nb, Z, nV, in, wp,
+                     part);
+  hipLaunchKernelGGL(k_proj_solve, dim3(1), dim3(kTriThreads), 0, s, (const double*)part, nblk, nb, Sinv, lo, uinv,
+                     tc, (const double*)wp, yp, yb, np);
+  hipLaunchKernelGGL(k_apply_CT_z, dim3(cdiv(nV, 256)), dim3(256), 0, s, geo, inc_off, inc, edge_path_row,
+                     (const double*)yp, Z, np, rows, (const double*)yb, nb, nV, in, out);
 }
 
 // ---------------------------------------------------------------------------

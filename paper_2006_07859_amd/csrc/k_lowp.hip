@@ -32,7 +32,8 @@
 //
 // Product Y = A^ X for X in R^{n x 3}, in difference form (see the product
 // section below): the B operand holds sqrt(d_w) (x_w - c) for a reference c
-// near the rows, scaled by a power of two into [-1, 1] (FP16 range) and split
+// near the rows, for FP16 scaled by a power of two into [-1, 1] (BF16 keeps
+// FP32's exponent range and needs no scaling), and split
 // into hi + lo 16-bit parts in columns 0-2 and 3-5, so one MFMA per A tile
 // gives both halves; the FP32 accumulators of the two halves are added, the
 // band and diagonal terms are applied in FP64, and the result is scaled back
@@ -272,6 +273,7 @@ __global__ __launch_bounds__(1024) void k_lowp_absmax(const double* __restrict__
 // Power-of-two factor that brings the bound into [0.5, 1): keeps the 16-bit
 // B operand inside the FP16 range whatever the scale of X and D.
 __device__ __forceinline__ double x_scale(const double* mx) {
+  if (!mx) return 1.0;  // BF16 operands: FP32's exponent range, no scaling needed
   const double m = mx[0];
   if (!(m > 0.0) || !isfinite(m)) return 1.0;
   int e;
@@ -441,25 +443,50 @@ __global__ __launch_bounds__(256) void k_lowp_gemv32(const float4* __restrict__ 
 
 // Y_v = sqrt(d_v) [ sum_splits part / sc + sigma_off_v sqrt(d_v) (x_v - c)
 //                  + sum_band S^_vw sqrt(d_w) (x_w - x_v) ]   (FP64; sc = 1 when mx is null)
-__global__ void k_lowp_finish(const float* __restrict__ part, int nsplit, const double* __restrict__ mx,
-                              const int* __restrict__ band_idx, const float* __restrict__ band_val, int band,
-                              const double* __restrict__ sigma_off, const double* __restrict__ sqd,
-                              const double* __restrict__ X, int n, double* __restrict__ Y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 3 * n) return;
-  const int v = i / 3, c = i % 3;
-  double s = 0.0;
-  for (int p = 0; p < nsplit; ++p) s += (double)part[(size_t)p * 3 * n + i];
-  if (mx) s /= x_scale(mx);
-  const double xv = X[i];
-  const double cr = X[3 * ((v / 64) * 64) + c];
-  s += sigma_off[v] * sqd[v] * (xv - cr);
-  const int nb = 2 * band;
-  for (int q = 0; q < nb; ++q) {
-    const int w = band_idx[(size_t)v * nb + q];
-    if (w >= 0) s += (double)band_val[(size_t)v * nb + q] * sqd[w] * (X[3 * w + c] - xv);
+// 32 lanes per vertex (two vertices per wave): lanes stride over the splits'
+// partial sums and the band entries, then a shuffle reduction over the 32.
+__global__ __launch_bounds__(256) void k_lowp_finish(const float* __restrict__ part, int nsplit,
+                                                     const double* __restrict__ mx, const int* __restrict__ band_idx,
+                                                     const float* __restrict__ band_val, int band,
+                                                     const double* __restrict__ sigma_off,
+                                                     const double* __restrict__ sqd, const double* __restrict__ X,
+                                                     int n, double* __restrict__ Y) {
+  const int h = threadIdx.x % 32;
+  const int v = (blockIdx.x * 256 + threadIdx.x) / 32;
+  const bool act = v < n;
+  const int vv = act ? v : 0;
+  const double isc = mx ? 1.0 / x_scale(mx) : 1.0;  // a power of two: exact
+  const double x0 = X[3 * vv], x1 = X[3 * vv + 1], x2 = X[3 * vv + 2];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int p = h; p < nsplit; p += 32) {
+    const float* q = part + ((size_t)p * n + vv) * 3;
+    s0 += (double)q[0] * isc;
+    s1 += (double)q[1] * isc;
+    s2 += (double)q[2] * isc;
   }
-  Y[i] = sqd[v] * s;
+  const int nb = 2 * band;
+  for (int q = h; q < nb; q += 32) {
+    const int w = band_idx[(size_t)vv * nb + q];
+    if (w >= 0) {
+      const double bw = (double)band_val[(size_t)vv * nb + q] * sqd[w];
+      s0 += bw * (X[3 * w] - x0);
+      s1 += bw * (X[3 * w + 1] - x1);
+      s2 += bw * (X[3 * w + 2] - x2);
+    }
+  }
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off, 32);
+    s1 += __shfl_xor(s1, off, 32);
+    s2 += __shfl_xor(s2, off, 32);
+  }
+  if (act && h < 3) {
+    const double sv = sqd[v];
+    const double xc = h == 0 ? x0 : h == 1 ? x1 : x2;
+    const double cr = X[3 * ((v / 64) * 64) + h];
+    const double sh = h == 0 ? s0 : h == 1 ? s1 : s2;
+    Y[3 * v + h] = sv * (sh + sigma_off[v] * sv * (xc - cr));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -621,16 +648,18 @@ static void prep(const LowpOp& op, const double* X, hipStream_t s) {
 template <typename T>
 static void apply16(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer) {
   typedef typename Vec8<T>::type V;
-  hipLaunchKernelGGL(k_lowp_absmax, dim3(1), dim3(1024), 0, s, X, op.sqd, op.n, op.mx);
+  // FP16 operands need the power-of-two scaling into range; BF16 ones do not
+  const double* mx = std::is_same<T, _Float16>::value ? (const double*)op.mx : nullptr;
+  if (mx) hipLaunchKernelGGL(k_lowp_absmax, dim3(1), dim3(1024), 0, s, X, op.sqd, op.n, op.mx);
   prep(op, X, s);
   const int waves = cdiv(op.nrb, kLowpRB) * op.nsplit;
   if (timer) timer->mark(timer->lowp, s);
   hipLaunchKernelGGL((k_lowp_gemv<T, kLowpRB>), dim3(cdiv(waves, 4)), dim3(256), 0, s, (const V*)op.tiles,
-                     (const float4*)op.pbuf, (const float4*)op.sqdf, (const double*)op.cref, (const double*)op.mx,
-                     op.n, op.nrb, op.nkt, op.nsplit, op.per, op.part);
+                     (const float4*)op.pbuf, (const float4*)op.sqdf, (const double*)op.cref, mx, op.n, op.nrb,
+                     op.nkt, op.nsplit, op.per, op.part);
   if (timer) timer->mark(timer->lowp, s);
-  hipLaunchKernelGGL(k_lowp_finish, dim3(cdiv(3 * op.n, 256)), dim3(256), 0, s, op.part, op.nsplit,
-                     (const double*)op.mx, op.band_idx, op.band_val, op.band, op.sigma, op.sqd, X, op.n, Y);
+  hipLaunchKernelGGL(k_lowp_finish, dim3(cdiv(op.n, 8)), dim3(256), 0, s, op.part, op.nsplit, mx, op.band_idx,
+                     op.band_val, op.band, op.sigma, op.sqd, X, op.n, Y);
 }
 
 rc_status launch_lowp_apply(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer) {
@@ -658,7 +687,7 @@ rc_status launch_lowp_apply32(const LowpOp& op, const double* X, double* Y, hipS
                      (const float4*)op.pbuf, (const float4*)op.sqdf, (const double*)op.cref, op.n, op.nrb, op.nkt,
                      op.nsplit, op.per, op.part);
   if (t) t->mark(t->asm32, s);
-  hipLaunchKernelGGL(k_lowp_finish, dim3(cdiv(3 * op.n, 256)), dim3(256), 0, s, op.part, op.nsplit,
+  hipLaunchKernelGGL(k_lowp_finish, dim3(cdiv(op.n, 8)), dim3(256), 0, s, op.part, op.nsplit,
                      (const double*)nullptr, op.band_idx, op.band_val, op.band, op.sigma32, op.sqd, X, op.n, Y);
   RC_HIP(hipGetLastError());
   return RC_OK;

@@ -27,6 +27,7 @@ struct Cons {
   double *Kpb = nullptr, *Z = nullptr, *Sinv = nullptr, *tri_scratch = nullptr;
   double *wp = nullptr, *yp = nullptr, *wb = nullptr, *yb = nullptr, *dots = nullptr, *rhs = nullptr;
   double* small = nullptr;
+  double* part = nullptr;  // partial sums of the three-launch projector
 };
 
 // Dense FP64 saddle solve on one curve: H = Abar + C^T C (Cholesky),

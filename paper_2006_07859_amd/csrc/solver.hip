@@ -192,7 +192,7 @@ void cons_free(Cons& k) {
   for (int* p : ip)
     if (p) hipFree(p);
   double* dp[] = {k.x0, k.len0, k.ones, k.geo, k.geo_eval, k.vals, k.rows, k.ta, k.td, k.tc, k.Kpb, k.Z, k.Sinv,
-                  k.tri_scratch, k.wp, k.yp, k.wb, k.yb, k.dots, k.rhs, k.small};
+                  k.tri_scratch, k.wp, k.yp, k.wb, k.yb, k.dots, k.rhs, k.small, k.part};
   for (double* p : dp)
     if (p) hipFree(p);
   k = Cons();
@@ -261,6 +261,7 @@ rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask) {
   RC_TRY(dalloc(&k.rhs, std::max(k.nb, 1)));
   RC_TRY(dalloc(&k.dots, (size_t)std::max(k.nb * k.nb, 4)));
   RC_TRY(dalloc(&k.small, (size_t)std::max(k.nb * k.nb, 8)));
+  RC_TRY(dalloc(&k.part, (size_t)64 * 2 * kProjMaxBorder));
   std::vector<double> ones(nE, 1.0);
   RC_HIP(hipMemcpy(k.ones, ones.data(), sizeof(double) * nE, hipMemcpyHostToDevice));
   RC_HIP(hipMemset(k.x0, 0, sizeof(double) * 3));
@@ -353,6 +354,12 @@ void cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double*
   const int nV = cv.nV;
   if (k.k == 0) {
     if (in != out) vec_copy(in, out, 3 * nV, s);
+    return;
+  }
+  if (k.nb <= kProjMaxBorder) {
+    cons_project_fused(k.geo, cv.edges, k.path_edge, k.np, k.rows, k.nb, k.Z, k.Sinv, k.tri_scratch,
+                       k.tri_scratch + k.np, k.tc, cv.inc_off, cv.inc, k.edge_path_row, nV, in, out, k.part, k.wp,
+                       k.yp, k.yb, s);
     return;
   }
   cons_path_apply(k.geo, cv.edges, k.path_edge, k.np, in, nV, 1, k.wp, s);
