@@ -182,40 +182,74 @@ void dense_cholesky(double* A, int n, int* info, hipStream_t s) {
   }
 }
 
-// L L^T X = B, B is n x m row-major: column sweeps, each workgroup owns up
-// to 16 right-hand-side columns.
+// L L^T X = B, B is n x m row-major; each workgroup owns up to 16
+// right-hand-side columns.
 constexpr int kSolveCols = 16;
+constexpr int kSolveRows = 32;  // row block of the blocked substitution
 
-__global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ L, double* __restrict__ B, int n,
-                                                      int m) {
+// Blocked substitution: for each block of 32 rows, the block's triangular
+// system is solved in LDS (one thread per right-hand-side column, no barriers
+// inside), then the rows after it (forward) or before it (backward) take a
+// rank-32 update.  512 threads per workgroup, kSolveCols columns.
+__global__ __launch_bounds__(512) void k_chol_solve(const double* __restrict__ L, double* __restrict__ B, int n,
+                                                     int m) {
+  __shared__ double Ld[kSolveRows][kSolveRows + 1];
+  __shared__ double Bb[kSolveRows][kSolveCols + 1];
+  const int tid = threadIdx.x;
   const int c0 = blockIdx.x * kSolveCols;
   const int mc = min(kSolveCols, m - c0);
   // forward: L y = b
-  for (int j = 0; j < n; ++j) {
-    const double ljj = L[(size_t)j * n + j];
-    if (threadIdx.x < mc) B[(size_t)j * m + c0 + threadIdx.x] /= ljj;
+  for (int j0 = 0; j0 < n; j0 += kSolveRows) {
+    const int nb = min(kSolveRows, n - j0);
+    for (int idx = tid; idx < nb * nb; idx += 512) Ld[idx / nb][idx % nb] = L[(size_t)(j0 + idx / nb) * n + j0 + idx % nb];
+    for (int idx = tid; idx < nb * mc; idx += 512) Bb[idx / mc][idx % mc] = B[(size_t)(j0 + idx / mc) * m + c0 + idx % mc];
     __syncthreads();
-    for (int idx = threadIdx.x; idx < (n - j - 1) * mc; idx += blockDim.x) {
-      int i = j + 1 + idx / mc, c = c0 + idx % mc;
-      B[(size_t)i * m + c] -= L[(size_t)i * n + j] * B[(size_t)j * m + c];
+    if (tid < mc) {
+      for (int i = 0; i < nb; ++i) {
+        double v = Bb[i][tid];
+        for (int jj = 0; jj < i; ++jj) v -= Ld[i][jj] * Bb[jj][tid];
+        Bb[i][tid] = v / Ld[i][i];
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nb * mc; idx += 512) B[(size_t)(j0 + idx / mc) * m + c0 + idx % mc] = Bb[idx / mc][idx % mc];
+    for (int idx = tid; idx < (n - j0 - nb) * mc; idx += 512) {
+      const int i = j0 + nb + idx / mc, c = idx % mc;
+      const double* Li = L + (size_t)i * n + j0;
+      double v = 0.0;
+      for (int jj = 0; jj < nb; ++jj) v += Li[jj] * Bb[jj][c];
+      B[(size_t)i * m + c0 + c] -= v;
     }
     __syncthreads();
   }
-  // backward: L^T x = y
-  for (int j = n - 1; j >= 0; --j) {
-    const double ljj = L[(size_t)j * n + j];
-    if (threadIdx.x < mc) B[(size_t)j * m + c0 + threadIdx.x] /= ljj;
+  // backward: L^T x = y, blocks from the last
+  for (int j0 = ((n - 1) / kSolveRows) * kSolveRows; j0 >= 0; j0 -= kSolveRows) {
+    const int nb = min(kSolveRows, n - j0);
+    for (int idx = tid; idx < nb * nb; idx += 512) Ld[idx / nb][idx % nb] = L[(size_t)(j0 + idx / nb) * n + j0 + idx % nb];
+    for (int idx = tid; idx < nb * mc; idx += 512) Bb[idx / mc][idx % mc] = B[(size_t)(j0 + idx / mc) * m + c0 + idx % mc];
     __syncthreads();
-    for (int idx = threadIdx.x; idx < j * mc; idx += blockDim.x) {
-      int i = idx / mc, c = c0 + idx % mc;
-      B[(size_t)i * m + c] -= L[(size_t)j * n + i] * B[(size_t)j * m + c];
+    if (tid < mc) {
+      for (int i = nb - 1; i >= 0; --i) {
+        double v = Bb[i][tid];
+        for (int jj = i + 1; jj < nb; ++jj) v -= Ld[jj][i] * Bb[jj][tid];
+        Bb[i][tid] = v / Ld[i][i];
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nb * mc; idx += 512) B[(size_t)(j0 + idx / mc) * m + c0 + idx % mc] = Bb[idx / mc][idx % mc];
+    // rows i < j0: b_i -= sum_jj L[j0 + jj][i] x_{j0 + jj}
+    for (int idx = tid; idx < j0 * mc; idx += 512) {
+      const int i = idx / mc, c = idx % mc;
+      double v = 0.0;
+      for (int jj = 0; jj < nb; ++jj) v += L[(size_t)(j0 + jj) * n + i] * Bb[jj][c];
+      B[(size_t)i * m + c0 + c] -= v;
     }
     __syncthreads();
   }
 }
 
 void dense_chol_solve(const double* L, double* B, int n, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_solve, dim3(cdiv(m, kSolveCols)), dim3(1024), 0, s, L, B, n, m);
+  hipLaunchKernelGGL(k_chol_solve, dim3(cdiv(m, kSolveCols)), dim3(512), 0, s, L, B, n, m);
 }
 
 // C[m x n] = op(A) op(B) + beta C, row-major; op(A) is m x k (A stored k x m
