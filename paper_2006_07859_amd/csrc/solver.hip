@@ -789,6 +789,14 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
   const rc_dtype op = o.op_f64 ? RC_F64 : c->dtype;
   const bool lowp = c->lowp_levels > 0;
   double *r = c->r, *z = c->z, *p = c->p, *q = c->q;
+  // Krylov operator: the assembled FP32 block (lowp_outer 1), the finest 16-bit
+  // block (lowp_outer 2, internal: loose projection-increment solves only), or
+  // the matrix-free operator in precision op
+  auto apply_op = [&](const double* X, double* Y) -> rc_status {
+    if (lowp && c->lowp_outer == 1 && o.lowp_outer == 1) return launch_lowp_apply32(c->lowp, X, Y, s, &c->timer);
+    if (lowp && o.lowp_outer == 2) return launch_lowp_apply(c->lowp, X, Y, s, nullptr);
+    return apply_A(c, c->curve, X, Y, op);
+  };
   c->last_sweeps = 0;
   cons_project(c, c->curve, c->cons, b, c->tmp2);  // P b
   vec_dot(c->tmp2, c->tmp2, n3, c->red, c->scal, s);
@@ -813,8 +821,7 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
     RC_TRY(fetch(c, c->scal, &rz, 1));
     int since = 0;
     while (it < o.max_iter) {
-      if (lowp && c->lowp_outer == 1) RC_TRY(launch_lowp_apply32(c->lowp, p, q, s, &c->timer));
-      else RC_TRY(apply_A(c, c->curve, p, q, op));
+      RC_TRY(apply_op(p, q));
       cons_project(c, c->curve, c->cons, q, q);
       vec_dot(p, q, n3, c->red, c->scal, s);
       double pq;
@@ -843,8 +850,9 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
       }
       if (res < std::max(o.tol, o.inner_tol * res_sweep) || (o.replace_every > 0 && since >= o.replace_every)) {
         // true residual r = P (b - Abar x) (FP64); restart the recurrence from it
-        // a loose solve (tol >= 1e-4) checks in its own operator's precision
-        RC_TRY(apply_A(c, c->curve, x, c->tmp, o.tol >= 1e-4 ? op : RC_F64));
+        // a loose solve (tol >= 1e-4) checks with its own operator
+        if (o.tol >= 1e-4) RC_TRY(apply_op(x, c->tmp));
+        else RC_TRY(apply_A(c, c->curve, x, c->tmp, RC_F64));
         vec_copy(b, r, n3, s);
         vec_axpby(-1.0, c->tmp, 1.0, r, n3, s);
         cons_project(c, c->curve, c->cons, r, r);
@@ -985,7 +993,8 @@ static rc_status projection_increment(rc_ctx* c, const double* phi, double* x, c
   }
   hipLaunchKernelGGL(k_negate, dim3(cdiv(k, 256)), dim3(256), 0, s, phi, c->phi + k, k);
   cons_min_norm(c, c->phi + k, c->zmin);
-  RC_TRY(apply_A(c, c->curve, c->zmin, c->inc, o.op_f64 ? RC_F64 : c->dtype));
+  if (o.lowp_outer == 2 && c->lowp_levels > 0) RC_TRY(launch_lowp_apply(c->lowp, c->zmin, c->inc, s, nullptr));
+  else RC_TRY(apply_A(c, c->curve, c->zmin, c->inc, o.op_f64 ? RC_F64 : c->dtype));
   double res = 0.0;
   rc_status st = pcg_solve(c, c->inc, c->x, o, iters, &res);
   if (st != RC_OK && st != RC_ERR_NOT_CONVERGED) return st;
@@ -1047,7 +1056,10 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
         // a loose increment solve: its operator runs in the context's precision
         // (C x = -Phi holds whatever the solve's accuracy)
         po.tol = ls.proj_solve_tol;
-        if (ls.proj_solve_tol >= 1e-4) po.op_f64 = 0;
+        if (ls.proj_solve_tol >= 1e-4) {
+          po.op_f64 = 0;
+          if (c->lowp_levels > 0) po.lowp_outer = 2;  // the finest 16-bit block, assembled at gamma
+        }
       }
       RC_TRY(projection_increment(c, c->phi, c->dx, po, &pit));
       out->proj_solve_iters += pit;
