@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--edges", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="default workload: skip the plain-multigrid comparison")
     ap.add_argument("--workload", default="step", choices=["step", "bh", "precision", "batch", "learned"],
                     help="step: projected Sobolev steps on the 16,384-edge knot (default); "
                          "bh: Barnes-Hut energy+differential on a 262,144-edge knot; "
@@ -219,6 +220,11 @@ def main():
     }
     # the same steps with the plain solver (FP32 matrix-free smoothers), from the same start
     ctx.close()
+    if args.no_plain:
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(g, e, alpha, beta)
+        print(json.dumps(out))
+        return
     ctx = Context(len(g), e, alpha, beta, RC_F32)
     gamma = dev(g)
     ctx.rc_set_constraints(RC_C_BARYCENTER | RC_C_EDGE_LENGTH, gamma)
