@@ -39,6 +39,45 @@ PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 
 
+CALIB_COPY_BYTES = 1 << 30  # the plain device copy that scales the HBM byte counters
+
+
+def calibration_copy():
+    """One device-to-device copy of CALIB_COPY_BYTES (1 GiB read + 1 GiB written): the reference
+    dispatch against which rocprofv3's FETCH_SIZE / WRITE_SIZE counters of the other kernels are scaled."""
+    import torch
+
+    src = torch.ones(CALIB_COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def traffic_record(kernel, edges):
+    """HBM bytes per launch of `kernel` on the `edges`-edge workload from the rocprofv3 counter summaries under profiles/
+    (FETCH_SIZE + WRITE_SIZE scaled by the copy calibration), or None when there is no record or a
+    source file it was measured with has changed since."""
+    import glob
+    import hashlib
+
+    key = kernel.split(" ")[0]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic-record: "):
+                continue
+            rec = json.loads(line[len("traffic-record: "):])
+            if rec["kernel"].split(" ")[0] != key or f"{edges} edges" not in rec["workload"]:
+                continue
+            for src, digest in rec["sources"].items():
+                f = os.path.join(ROOT, src)
+                if not os.path.exists(f) or hashlib.sha256(open(f, "rb").read()).hexdigest() != digest:
+                    return None
+            return rec["traffic_bytes"]
+    return None
+
+
 def ordered_disjoint_pairs(edges):
     import numpy as np
 
@@ -124,6 +163,7 @@ def main():
     g = gen.round_to_f32(g)
     P = ordered_disjoint_pairs(e)
     torch.cuda.init()
+    calibration_copy()
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     ctx = Context(len(g), e, alpha, beta, RC_F32)
     gamma = dev(g)
@@ -177,10 +217,11 @@ def main():
         avg = ms / nl * 1e-3
         ach = work / avg
         rooflines.append({"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
-                          "frac": round(ach / peak, 4), "traffic": None, "kernel": name,
+                          "frac": round(ach / peak, 4), "traffic": traffic_record(name, n), "kernel": name,
                           "avg_launch_ms": round(avg * 1e3, 4), "launches": nl, "total_ms": round(ms, 2)})
     # the dominant kernel of the step: the largest total time among the timed ones
     roofline = max(rooflines, key=lambda r: r["total_ms"])
+    roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     out = {
         "metric": "edge-pair evals/s (energy+grad)",
         "value": value,
@@ -348,6 +389,7 @@ def bench_precision(args):
     n = 32768 if args.edges == 16384 else args.edges
     alpha, beta = 2.0, 4.5
     fmt = {"bf16": 1, "fp16": 2}[args.fmt]
+    calibration_copy()
     g, e, _ = gen.fourier_knot(n, seed=0)
     g = gen.round_to_f32(g)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
@@ -433,7 +475,8 @@ def bench_precision(args):
                                f"projected PCG to 1e-8 FP64 residual with {args.fmt} smoothers on levels >= 4096 "
                                f"vertices and the FP64 matrix-free Krylov operator", "edges": n},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
-                     "frac": round(gbs / 8000.0, 4), "traffic": None,
+                     "frac": round(gbs / 8000.0, 4), "traffic": traffic_record(f"k_lowp_gemv<{args.fmt}>", n),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": f"k_lowp_gemv<{args.fmt}> (finest level)", "launches": lp_n,
                      "avg_launch_ms": round(avg * 1e3, 4), "bytes_per_launch": bytes_per},
         "mfma_products_per_s": 1.0 / avg,
