@@ -503,9 +503,11 @@ __global__ __launch_bounds__(256) void k_gj_update(int k, const int* __restrict_
 __global__ __launch_bounds__(256) void k_b_prec(const int2* __restrict__ prec_items,
                                                 const int* __restrict__ chain_vert, const int* __restrict__ chain_voff,
                                                 const long long* __restrict__ blk_off, const double* __restrict__ Minv,
+                                                const int* __restrict__ chain_inst, const int* __restrict__ mask,
                                                 const double* __restrict__ r, double* __restrict__ z) {
   const int2 it = prec_items[blockIdx.x];
   const int q = it.x;
+  if (mask && !mask[chain_inst[q]]) return;  // instance no longer iterating: z is not used
   const int m = chain_voff[q + 1] - chain_voff[q];
   const int* vs = chain_vert + chain_voff[q];
   const double* M = Minv + blk_off[q];
@@ -956,10 +958,11 @@ static rc_status b_prepare(rc_ctx* c) {
 }
 
 // z = P M^-1 P r (r already in range P).
-static void b_precondition(rc_ctx* c, const double* r, double* z) {
+// mask (may be null): instances whose z is needed (the others keep stale values)
+static void b_precondition(rc_ctx* c, const double* r, double* z, const int* mask) {
   Batch& B = c->batch;
   hipLaunchKernelGGL(k_b_prec, dim3(B.n_prec), dim3(256), 0, c->stream, B.prec_items, B.chain_vert, B.chain_voff,
-                     B.blk_off, B.Minv, r, z);
+                     B.blk_off, B.Minv, (const int*)B.chain_inst, mask, r, z);
   b_project(c, z, z);
 }
 
@@ -985,7 +988,7 @@ static rc_status b_pcg(rc_ctx* c, const double* rhs, double* x, double tol, int 
   hipLaunchKernelGGL(k_b_fill, gv, bv, 0, s, x, (size_t)n3, 0.0);
   hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.r, B.r, vo, B.sc, kBatchScal, (int)S_RR);
   hipLaunchKernelGGL(k_b_pcg_start, gi, bi, 0, s, B.sc, B.n_inst, ls_mask);
-  b_precondition(c, B.r, B.z);
+  b_precondition(c, B.r, B.z, nullptr);
   hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.r, B.z, vo, B.sc, kBatchScal, (int)S_RZ);
   hipLaunchKernelGGL(k_b_copy, gv, bv, 0, s, B.z, B.p, n3);
   for (int it = 0; it < max_it; ++it) {
@@ -998,7 +1001,7 @@ static rc_status b_pcg(rc_ctx* c, const double* rhs, double* x, double tol, int 
     hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.p, B.q, vo, B.sc, kBatchScal, (int)S_PQ);
     hipLaunchKernelGGL(k_b_pcg_alpha, gi, bi, 0, s, B.sc, B.n_inst);
     hipLaunchKernelGGL(k_b_xr, gv, bv, 0, s, iv, B.sc, nV, B.p, B.q, x, B.r);
-    b_precondition(c, B.r, B.z);
+    b_precondition(c, B.r, B.z, B.mask);
     hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.r, B.r, vo, B.sc, kBatchScal, (int)S_RR);
     hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.r, B.z, vo, B.sc, kBatchScal, (int)S_BETA);
     hipLaunchKernelGGL(k_b_pcg_beta, gi, bi, 0, s, B.sc, B.n_inst, tol, it);
