@@ -113,6 +113,8 @@ typedef struct {
   int32_t graph;         /* 1 = capture the whole step in a hipGraph on first use and replay it */
   int32_t check_every;   /* without graph: stop the PCG once every instance has converged, checked
                             every check_every iterations (0 = run max_iter) */
+  int32_t coarse;        /* 1 = two-level preconditioner: loop blocks plus the coarse space of per-loop
+                            translations (instances of at most 64 loops); 0 = loop blocks only */
 } rc_batch_opts;
 
 typedef struct {

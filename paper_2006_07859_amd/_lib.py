@@ -57,7 +57,8 @@ class SolveOpts(C.Structure):
 class BatchOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("ls_rounds", C.c_int32), ("proj_iters", C.c_int32),
                 ("proj_max_iter", C.c_int32), ("proj_tol", C.c_double), ("accept_tol", C.c_double),
-                ("c_armijo", C.c_double), ("tau0", C.c_double), ("graph", C.c_int32), ("check_every", C.c_int32)]
+                ("c_armijo", C.c_double), ("tau0", C.c_double), ("graph", C.c_int32), ("check_every", C.c_int32),
+                ("coarse", C.c_int32)]
 
 
 class LsOpts(C.Structure):

@@ -577,7 +577,7 @@ extern "C" rc_status rc_batch_autotune(rc_ctx* c, const double* gamma, const cha
 extern "C" void rc_default_batch_opts(rc_batch_opts* o) {
   if (!o) return;
   o->tol = 1e-4;
-  o->max_iter = 120;
+  o->max_iter = 60;
   o->ls_rounds = 4;
   o->proj_iters = 2;
   o->proj_max_iter = 10;
@@ -587,6 +587,7 @@ extern "C" void rc_default_batch_opts(rc_batch_opts* o) {
   o->tau0 = 1.0;
   o->graph = 0;
   o->check_every = 5;
+  o->coarse = 1;
 }
 
 static rc_status batch_ctx(rc_ctx* c, const char* name) {
@@ -602,7 +603,8 @@ static rc_status batch_opts(const rc_batch_opts* in, rc_batch_opts* o) {
   rc_default_batch_opts(o);
   if (in) *o = *in;
   if (!(o->tol > 0) || o->max_iter < 1 || o->ls_rounds < 1 || o->proj_iters < 0 || o->proj_max_iter < 1 ||
-      !(o->proj_tol > 0) || !(o->accept_tol > 0) || !(o->c_armijo > 0) || !(o->tau0 > 0) || o->check_every < 0) {
+      !(o->proj_tol > 0) || !(o->accept_tol > 0) || !(o->c_armijo > 0) || !(o->tau0 > 0) || o->check_every < 0 ||
+      (o->coarse != 0 && o->coarse != 1)) {
     set_error("batch options out of range");
     return RC_ERR_ARG;
   }

@@ -504,7 +504,8 @@ __global__ __launch_bounds__(256) void k_b_prec(const int2* __restrict__ prec_it
                                                 const int* __restrict__ chain_vert, const int* __restrict__ chain_voff,
                                                 const long long* __restrict__ blk_off, const double* __restrict__ Minv,
                                                 const int* __restrict__ chain_inst, const int* __restrict__ mask,
-                                                const double* __restrict__ r, double* __restrict__ z) {
+                                                const double* __restrict__ cl, const double* __restrict__ r,
+                                                double* __restrict__ z) {
   const int2 it = prec_items[blockIdx.x];
   const int q = it.x;
   if (mask && !mask[chain_inst[q]]) return;  // instance no longer iterating: z is not used
@@ -528,11 +529,204 @@ __global__ __launch_bounds__(256) void k_b_prec(const int2* __restrict__ prec_it
     }
     if (lane == 0) {
       const int v = vs[a];
-      z[3 * v] = s0;
-      z[3 * v + 1] = s1;
-      z[3 * v + 2] = s2;
+      const double c0 = cl ? cl[3 * q] : 0.0, c1 = cl ? cl[3 * q + 1] : 0.0, c2 = cl ? cl[3 * q + 2] : 0.0;
+      z[3 * v] = s0 + c0;  // + the coarse correction of the loop
+      z[3 * v + 1] = s1 + c1;
+      z[3 * v + 2] = s2 + c2;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// coarse space of per-loop translations
+// ---------------------------------------------------------------------------
+// The high-order part B annihilates a function that is constant on one loop
+// and zero elsewhere (every edge lies inside one loop), so the Galerkin
+// matrix of the per-loop translations (one per loop and component) is that
+// of B0 alone: the graph Laplacian of the loops with weights
+//   W[q][q'] = 1/4 sum_{I in q, J in q'} l_I l_J rho0_IJ,
+// rho0 the low-order pair weight of the operator (sum over the four vertex
+// pairs of |d|^-(2 sigma + 1) (|T_I x d|^2 + |T_J x d|^2) / |d|^4).  Loop-block
+// Jacobi misses exactly these modes; adding R^T A0^-1 R gives the two-level
+// preconditioner (R: per-loop sums).
+//
+// k_b_coupling: one workgroup per (instance, 256 target edges in loop order);
+// every target sweeps the instance's edges in loop order and writes one sum
+// per source loop at each loop boundary (the boundaries are the same for all
+// threads), its own loop as 0.
+template <int EC>
+__global__ __launch_bounds__(256) void k_b_coupling(const V4<float>* __restrict__ GA, const V4<float>* __restrict__ GB,
+                                                    const V4<float>* __restrict__ GT,
+                                                    const int* __restrict__ chain_edges,
+                                                    const int* __restrict__ cedge_loop,
+                                                    const int* __restrict__ inst_qoff,
+                                                    const int* __restrict__ inst_ceoff, const int2* __restrict__ items,
+                                                    int max_loops, float half_expo, float* __restrict__ Wp) {
+  __shared__ V4<float> sA[256], sB[256], sT[256];
+  __shared__ int sL[256];
+  const int2 it = items[blockIdx.x];
+  const int i = it.x, tid = threadIdx.x;
+  const int e0 = inst_ceoff[i], e1 = inst_ceoff[i + 1];
+  const int kI = e0 + it.y + tid;
+  const bool act = kI < e1;
+  const int I = chain_edges[act ? kI : e0];
+  const V4<float> a = GA[I], b = GB[I], t = GT[I];
+  const int myloop = act ? cedge_loop[kI] : -1;
+  const int q0 = inst_qoff[i];
+  int cur = cedge_loop[e0];
+  float acc = 0.f;
+  for (int s0 = e0; s0 < e1; s0 += 256) {
+    __syncthreads();
+    if (s0 + tid < e1) {
+      const int J = chain_edges[s0 + tid];
+      sA[tid] = GA[J];
+      sB[tid] = GB[J];
+      sT[tid] = GT[J];
+      sL[tid] = cedge_loop[s0 + tid];
+    }
+    __syncthreads();
+    const int cnt = min(256, e1 - s0);
+    for (int u = 0; u < cnt; ++u) {
+      const int lj = sL[u];
+      if (lj != cur) {  // the same for every thread of the workgroup
+        if (act) Wp[(size_t)kI * max_loops + (cur - q0)] = cur == myloop ? 0.f : 0.25f * a.w * acc;
+        acc = 0.f;
+        cur = lj;
+      }
+      if (lj == myloop) continue;
+      const V4<float> qa = sA[u], qb = sB[u], qt = sT[u];
+      float rho0 = 0.f;
+#define RC_CPL_VP(PX, QX)                                                          \
+  {                                                                                \
+    const float dx = PX.x - QX.x, dy = PX.y - QX.y, dz = PX.z - QX.z;             \
+    const float r2 = dx * dx + dy * dy + dz * dz;                                  \
+    const float rs = f_rsq<float>(r2), ri = rs * rs;                               \
+    const float p = pow_sigma<EC, float>(r2, rs, ri, half_expo);                   \
+    rho0 += p * (cross_norm2<float>(t.x, t.y, t.z, dx, dy, dz) +                   \
+                 cross_norm2<float>(qt.x, qt.y, qt.z, dx, dy, dz)) * ri * ri;      \
+  }
+      RC_CPL_VP(a, qa)
+      RC_CPL_VP(a, qb)
+      RC_CPL_VP(b, qa)
+      RC_CPL_VP(b, qb)
+#undef RC_CPL_VP
+      acc += qa.w * rho0;
+    }
+  }
+  if (act) Wp[(size_t)kI * max_loops + (cur - q0)] = cur == myloop ? 0.f : 0.25f * a.w * acc;
+}
+
+// W[i][q][q'] = sum over the edges of loop q of Wp[.][q'] (one workgroup per loop).
+__global__ __launch_bounds__(64) void k_b_coupling_reduce(const float* __restrict__ Wp,
+                                                          const int* __restrict__ chain_eoff,
+                                                          const int* __restrict__ chain_inst,
+                                                          const int* __restrict__ inst_qoff, int max_loops,
+                                                          double* __restrict__ Wc) {
+  const int q = blockIdx.x, i = chain_inst[q];
+  const int q0 = inst_qoff[i], nl = inst_qoff[i + 1] - q0;
+  const int j = threadIdx.x;
+  if (j >= nl) return;
+  double s = 0.0;
+  for (int k = chain_eoff[q]; k < chain_eoff[q + 1]; ++k) s += (double)Wp[(size_t)k * max_loops + j];
+  Wc[(size_t)i * max_loops * max_loops + (size_t)(q - q0) * max_loops + j] = s;
+}
+
+// A0 = diag(row sums of W_sym) - W_sym + c 1 1^T (c = trace / nl^2 removes the
+// constant null vector), inverted in place by Gauss-Jordan (SPD: no pivoting);
+// one workgroup per instance.  A single loop (or no coupling) gets A0^-1 = 0.
+constexpr int kCoarseMax = 64;
+__global__ __launch_bounds__(256) void k_b_coarse_inv(const double* __restrict__ Wc, const int* __restrict__ inst_qoff,
+                                                      int max_loops, double* __restrict__ Ainv) {
+  __shared__ double M[kCoarseMax][kCoarseMax + 1];
+  __shared__ double fcol[kCoarseMax];
+  __shared__ double tr;
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const int nl = inst_qoff[i + 1] - inst_qoff[i];
+  const double* W = Wc + (size_t)i * max_loops * max_loops;
+  double* out = Ainv + (size_t)i * max_loops * max_loops;
+  for (int e = tid; e < nl * nl; e += 256) {
+    const int r = e / nl, c = e % nl;
+    M[r][c] = r == c ? 0.0 : -0.5 * (W[r * max_loops + c] + W[c * max_loops + r]);
+  }
+  __syncthreads();
+  if (tid < nl) {
+    double d = 0.0;
+    for (int c = 0; c < nl; ++c) d -= M[tid][c];
+    M[tid][tid] = d;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int r = 0; r < nl; ++r) t += M[r][r];
+    tr = t;
+  }
+  __syncthreads();
+  const bool none = nl < 2 || !(tr > 0.0);
+  if (none) {
+    for (int e = tid; e < nl * nl; e += 256) out[(e / nl) * max_loops + e % nl] = 0.0;
+    return;
+  }
+  const double reg = tr / ((double)nl * nl);
+  for (int e = tid; e < nl * nl; e += 256) M[e / nl][e % nl] += reg;
+  __syncthreads();
+  for (int k = 0; k < nl; ++k) {
+    const double piv = 1.0 / M[k][k];
+    if (tid < nl) fcol[tid] = M[tid][k];
+    __syncthreads();
+    if (tid < nl) M[k][tid] = tid == k ? piv : M[k][tid] * piv;
+    __syncthreads();
+    for (int e = tid; e < nl * nl; e += 256) {
+      const int r = e / nl, c = e % nl;
+      if (r == k) continue;
+      if (c == k) M[r][c] = -fcol[r] * piv;
+      else M[r][c] -= fcol[r] * M[k][c];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nl * nl; e += 256) out[(e / nl) * max_loops + e % nl] = M[e / nl][e % nl];
+}
+
+// rsum[q] = sum of r over loop q's vertices (one workgroup per loop).
+__global__ __launch_bounds__(256) void k_b_loop_rsum(const int* __restrict__ chain_vert,
+                                                     const int* __restrict__ chain_voff,
+                                                     const int* __restrict__ chain_inst, const int* __restrict__ mask,
+                                                     const double* __restrict__ r, double* __restrict__ rsum) {
+  __shared__ double sm[256];
+  const int q = blockIdx.x;
+  if (mask && !mask[chain_inst[q]]) return;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int k = chain_voff[q] + threadIdx.x; k < chain_voff[q + 1]; k += 256) {
+    const int v = chain_vert[k];
+    s[0] += r[3 * v];
+    s[1] += r[3 * v + 1];
+    s[2] += r[3 * v + 2];
+  }
+  for (int c = 0; c < 3; ++c) {
+    const double t = block_sum(s[c], sm);
+    if (threadIdx.x == 0) rsum[3 * q + c] = t;
+    __syncthreads();
+  }
+}
+
+// cl[q] = sum_q' A0^-1[q][q'] rsum[q'] within each instance (one workgroup per instance).
+__global__ __launch_bounds__(64) void k_b_coarse_apply(const double* __restrict__ Ainv,
+                                                       const int* __restrict__ inst_qoff, int max_loops,
+                                                       const int* __restrict__ mask,
+                                                       const double* __restrict__ rsum, double* __restrict__ cl) {
+  const int i = blockIdx.x, q = threadIdx.x;
+  if (mask && !mask[i]) return;
+  const int q0 = inst_qoff[i], nl = inst_qoff[i + 1] - q0;
+  if (q >= nl) return;
+  const double* A = Ainv + (size_t)i * max_loops * max_loops + (size_t)q * max_loops;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int j = 0; j < nl; ++j) {
+    s0 += A[j] * rsum[3 * (q0 + j)];
+    s1 += A[j] * rsum[3 * (q0 + j) + 1];
+    s2 += A[j] * rsum[3 * (q0 + j) + 2];
+  }
+  cl[3 * (q0 + q)] = s0;
+  cl[3 * (q0 + q) + 1] = s1;
+  cl[3 * (q0 + q) + 2] = s2;
 }
 
 // ---------------------------------------------------------------------------
@@ -845,6 +1039,35 @@ rc_status batch_alloc(rc_ctx* c) {
     RC_TRY(balloc(&B.prec_items, pit.size()));
     RC_HIP(hipMemcpy(B.prec_items, pit.data(), sizeof(int2) * pit.size(), hipMemcpyHostToDevice));
   }
+  // coarse space: loop of every chain-ordered edge, chain-edge range of every
+  // instance, coupling work items (instance, 256 targets); off when an
+  // instance has more than kCoarseMax loops
+  {
+    B.max_loops = 0;
+    for (int i = 0; i < B.n_inst; ++i) B.max_loops = std::max(B.max_loops, qoff[i + 1] - qoff[i]);
+    B.coarse = B.max_loops >= 2 && B.max_loops <= kCoarseMax;
+    if (B.coarse) {
+      std::vector<int> cel(nE), iceoff(B.n_inst + 1);
+      for (int q = 0; q < B.nq; ++q)
+        for (int k = ceoff[q]; k < ceoff[q + 1]; ++k) cel[k] = q;
+      for (int i = 0; i <= B.n_inst; ++i) iceoff[i] = ceoff[qoff[i]];
+      std::vector<int2> cit;
+      for (int i = 0; i < B.n_inst; ++i)
+        for (int t0 = 0; t0 < iceoff[i + 1] - iceoff[i]; t0 += 256) cit.push_back(make_int2(i, t0));
+      B.n_cpl = (int)cit.size();
+      RC_TRY(balloc(&B.cedge_loop, nE));
+      RC_TRY(balloc(&B.inst_ceoff, B.n_inst + 1));
+      RC_TRY(balloc(&B.cpl_items, cit.size()));
+      RC_TRY(balloc(&B.Wp, (size_t)nE * B.max_loops));
+      RC_TRY(balloc(&B.Wc, (size_t)B.n_inst * B.max_loops * B.max_loops));
+      RC_TRY(balloc(&B.Ainv, (size_t)B.n_inst * B.max_loops * B.max_loops));
+      RC_TRY(balloc(&B.rsum, 3 * (size_t)B.nq));
+      RC_TRY(balloc(&B.cl, 3 * (size_t)B.nq));
+      RC_HIP(hipMemcpy(B.cedge_loop, cel.data(), sizeof(int) * nE, hipMemcpyHostToDevice));
+      RC_HIP(hipMemcpy(B.inst_ceoff, iceoff.data(), sizeof(int) * (B.n_inst + 1), hipMemcpyHostToDevice));
+      RC_HIP(hipMemcpy(B.cpl_items, cit.data(), sizeof(int2) * cit.size(), hipMemcpyHostToDevice));
+    }
+  }
   RC_TRY(balloc(&B.x0, 3 * (size_t)B.n_inst));
   RC_TRY(balloc(&B.L0, B.nq));
   RC_TRY(balloc(&B.Jv, 9 * (size_t)nV));
@@ -877,7 +1100,8 @@ void batch_free(rc_ctx* c) {
   void* ps[] = {B.chain_vert, B.chain_voff, B.chain_of_vertex, B.chain_inst, B.inst_qoff, B.chain_eoff,
                 B.chain_edges, B.blk_off, B.Minv, B.gj_col, B.x0, B.L0, B.Jv, B.Lv, B.qsum, B.Sinv, B.cq,
                 B.yb, B.yq, B.dvec, B.x, B.r, B.z, B.p, B.q, B.b, B.t, B.trial, B.ghat, B.dE, B.g, B.inc,
-                B.sc, B.ls, B.energy, B.stats, B.phiq, B.phib, B.mask, B.gj_list, B.gj_pre, B.prec_items};
+                B.sc, B.ls, B.energy, B.stats, B.phiq, B.phib, B.mask, B.gj_list, B.gj_pre, B.prec_items,
+                B.cedge_loop, B.inst_ceoff, B.cpl_items, B.Wp, B.Wc, B.Ainv, B.rsum, B.cl};
   for (void* p : ps)
     if (p) hipFree(p);
   B = Batch();
@@ -953,6 +1177,22 @@ static rc_status b_prepare(rc_ctx* c) {
     hipLaunchKernelGGL(k_gj_update, dim3(B.h_gj_tiles[k]), dim3(256), 0, s, k, B.gj_list + off, B.gj_pre + off, nact,
                        B.chain_voff, B.blk_off, B.Minv, (const double*)B.gj_col);
   }
+  if (B.use_coarse) {  // loop couplings (FP32 pair sums, FP32 geometry of gamma) and the coarse inverses
+#define RC_CPL(EC)                                                                                             \
+  hipLaunchKernelGGL((k_b_coupling<EC>), dim3(B.n_cpl), dim3(256), 0, s, cv.gf.a, cv.gf.b, cv.gf.t, B.chain_edges, \
+                     (const int*)B.cedge_loop, B.inst_qoff, (const int*)B.inst_ceoff, (const int2*)B.cpl_items,    \
+                     B.max_loops, (float)half_expo, B.Wp)
+    switch (exp_case(c->alpha, c->beta)) {
+      case kA2B4: RC_CPL(kA2B4); break;
+      case kA2B45: RC_CPL(kA2B45); break;
+      default: RC_CPL(kGeneral); break;
+    }
+#undef RC_CPL
+    hipLaunchKernelGGL(k_b_coupling_reduce, dim3(B.nq), dim3(64), 0, s, (const float*)B.Wp, B.chain_eoff,
+                       (const int*)B.chain_inst, B.inst_qoff, B.max_loops, B.Wc);
+    hipLaunchKernelGGL(k_b_coarse_inv, dim3(B.n_inst), dim3(256), 0, s, (const double*)B.Wc, B.inst_qoff,
+                       B.max_loops, B.Ainv);
+  }
   RC_HIP(hipGetLastError());
   return RC_OK;
 }
@@ -961,8 +1201,16 @@ static rc_status b_prepare(rc_ctx* c) {
 // mask (may be null): instances whose z is needed (the others keep stale values)
 static void b_precondition(rc_ctx* c, const double* r, double* z, const int* mask) {
   Batch& B = c->batch;
-  hipLaunchKernelGGL(k_b_prec, dim3(B.n_prec), dim3(256), 0, c->stream, B.prec_items, B.chain_vert, B.chain_voff,
-                     B.blk_off, B.Minv, (const int*)B.chain_inst, mask, r, z);
+  hipStream_t s = c->stream;
+  if (B.use_coarse) {
+    hipLaunchKernelGGL(k_b_loop_rsum, dim3(B.nq), dim3(256), 0, s, B.chain_vert, B.chain_voff,
+                       (const int*)B.chain_inst, mask, r, B.rsum);
+    hipLaunchKernelGGL(k_b_coarse_apply, dim3(B.n_inst), dim3(64), 0, s, (const double*)B.Ainv, B.inst_qoff,
+                       B.max_loops, mask, (const double*)B.rsum, B.cl);
+  }
+  hipLaunchKernelGGL(k_b_prec, dim3(B.n_prec), dim3(256), 0, s, B.prec_items, B.chain_vert, B.chain_voff,
+                     B.blk_off, B.Minv, (const int*)B.chain_inst, mask, B.use_coarse ? (const double*)B.cl : nullptr,
+                     r, z);
   b_project(c, z, z);
 }
 
@@ -1023,6 +1271,7 @@ rc_status batch_gradient(rc_ctx* c, const double* gamma, const double* dE, doubl
     set_error("batch constraints not set (rc_batch_set_constraints)");
     return RC_ERR_ARG;
   }
+  c->batch.use_coarse = c->batch.coarse && o.coarse != 0;
   RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));
   RC_TRY(b_prepare(c));
   return b_pcg(c, dE, g, o.tol, o.max_iter, o.check_every, nullptr);
@@ -1032,6 +1281,7 @@ rc_status batch_gradient(rc_ctx* c, const double* gamma, const double* dE, doubl
 // check_every == 0.  gamma is updated in place per instance.
 static rc_status b_step(rc_ctx* c, double* gamma, const rc_batch_opts& o, int check_every) {
   Batch& B = c->batch;
+  B.use_coarse = B.coarse && o.coarse != 0;
   Curve& cv = c->curve;
   hipStream_t s = c->stream;
   const int nV = c->nV, n3 = 3 * nV;
@@ -1102,7 +1352,13 @@ rc_status batch_step(rc_ctx* c, double* gamma, const rc_batch_opts& o, double* s
     return RC_ERR_ARG;
   }
   if (o.graph) {
-    const bool same = B.captured && B.cap_gamma == gamma && std::memcmp(&B.cap_opts, &o, sizeof(o)) == 0;
+    const rc_batch_opts& k = B.cap_opts;  // field by field: the struct has tail padding
+    const bool same_opts = k.tol == o.tol && k.max_iter == o.max_iter && k.ls_rounds == o.ls_rounds &&
+                           k.proj_iters == o.proj_iters && k.proj_max_iter == o.proj_max_iter &&
+                           k.proj_tol == o.proj_tol && k.accept_tol == o.accept_tol && k.c_armijo == o.c_armijo &&
+                           k.tau0 == o.tau0 && k.graph == o.graph && k.check_every == o.check_every &&
+                           k.coarse == o.coarse;
+    const bool same = B.captured && B.cap_gamma == gamma && same_opts;
     if (!same) {
       if (B.exec) hipGraphExecDestroy(B.exec);
       if (B.graph) hipGraphDestroy(B.graph);

@@ -82,6 +82,15 @@ struct Batch {
   std::vector<int> h_gj_step_off, h_gj_tiles;
   int *gj_list = nullptr, *gj_pre = nullptr;
   int2* prec_items = nullptr;
+  // coarse space of per-loop translations (two-level preconditioner)
+  bool coarse = false;      // available (every instance has at most kCoarseMax loops)
+  bool use_coarse = false;  // chosen by the options of the current solve
+  int max_loops = 0, n_cpl = 0;
+  int *cedge_loop = nullptr, *inst_ceoff = nullptr;
+  int2* cpl_items = nullptr;
+  float* Wp = nullptr;                 // [nE][max_loops] per-target-edge couplings
+  double *Wc = nullptr, *Ainv = nullptr;  // [n_inst][max_loops^2]
+  double *rsum = nullptr, *cl = nullptr;  // [nq][3]
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;

