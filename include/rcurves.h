@@ -115,6 +115,9 @@ typedef struct {
                             every check_every iterations (0 = run max_iter) */
   int32_t coarse;        /* 1 = two-level preconditioner: loop blocks plus the coarse space of per-loop
                             translations (instances of at most 64 loops); 0 = loop blocks only */
+  int32_t op_assembled;  /* 1 = the solves' operator is each instance's block of Abar assembled in FP32
+                            once per step at gamma (sum of n_i^2 * 4 bytes of device memory, allocated on
+                            first use), applied in difference form; 0 = the matrix-free FP32 operator */
 } rc_batch_opts;
 
 typedef struct {
@@ -360,6 +363,12 @@ rc_status rc_batch_gradient(rc_ctx* ctx, const double* gamma, const double* dE, 
  * PCG residual, status 0 accepted / 1 no step / 2 singular constraints, |g|,
  * halvings); filling it synchronises. */
 rc_status rc_batch_step(rc_ctx* ctx, double* gamma, const rc_batch_opts* opts, double* stats_h);
+
+/* Y = Abar X for every instance at gamma with the FP32 operator: matrix-free
+ * (assembled = 0) or from the per-instance blocks assembled at gamma
+ * (assembled = 1, the operator of rc_batch_opts.op_assembled).  X, Y: device
+ * double[nV][3]. */
+rc_status rc_batch_sobolev_apply(rc_ctx* ctx, const double* gamma, const double* X, double* Y, int32_t assembled);
 
 /* Iterations and relative residual of every instance in the last batch PCG
  * solve (host double[n_inst] each); synchronises. */

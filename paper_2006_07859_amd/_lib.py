@@ -34,7 +34,7 @@ EXPORTED = [
     "rc_profile_enable", "rc_profile_read", "rc_lowp_assemble", "rc_lowp_apply", "rc_set_obstacle",
     "rc_create_batch", "rc_batch_size", "rc_batch_energies", "rc_batch_tiling", "rc_default_batch_opts",
     "rc_batch_set_constraints", "rc_batch_gradient", "rc_batch_step", "rc_batch_pcg_state", "rc_batch_autotune",
-    "rc_mlp_n_params", "rc_mlp_create", "rc_mlp_destroy", "rc_mlp_get", "rc_mlp_set", "rc_mlp_forward",
+    "rc_batch_sobolev_apply", "rc_mlp_n_params", "rc_mlp_create", "rc_mlp_destroy", "rc_mlp_get", "rc_mlp_set", "rc_mlp_forward",
     "rc_mlp_backward", "rc_mlp_adam", "rc_learned_attach", "rc_learned_levels", "rc_learned_features",
     "rc_learned_scalings", "rc_learned_apply", "rc_learned_train_step",
 ]
@@ -58,7 +58,7 @@ class BatchOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("ls_rounds", C.c_int32), ("proj_iters", C.c_int32),
                 ("proj_max_iter", C.c_int32), ("proj_tol", C.c_double), ("accept_tol", C.c_double),
                 ("c_armijo", C.c_double), ("tau0", C.c_double), ("graph", C.c_int32), ("check_every", C.c_int32),
-                ("coarse", C.c_int32)]
+                ("coarse", C.c_int32), ("op_assembled", C.c_int32)]
 
 
 class LsOpts(C.Structure):
@@ -128,6 +128,7 @@ def load():
         "rc_batch_pcg_state": (I32, [P, P, P]),
         "rc_batch_autotune": (I32, [P, P, C.c_char_p, C.POINTER(I32), C.POINTER(I32), C.POINTER(D)]),
         "rc_lowp_apply": (I32, [P, P, P, I32]),
+        "rc_batch_sobolev_apply": (I32, [P, P, P, P, I32]),
         "rc_mlp_n_params": (I32, []),
         "rc_mlp_create": (I32, [P, P, C.POINTER(P)]),
         "rc_mlp_destroy": (I32, [P]),
@@ -483,6 +484,10 @@ class Batch(Context):
         path = None if cache_path is None else str(cache_path).encode()
         _check(load().rc_batch_autotune(self.h, self._v(gamma, "gamma"), path, C.byref(a), C.byref(b), C.byref(ms)))
         return {"src_chunk": a.value, "blocks_per_cu": b.value, "ms": ms.value}
+
+    def rc_batch_sobolev_apply(self, gamma, X, Y, assembled=True):
+        _check(load().rc_batch_sobolev_apply(self.h, self._v(gamma, "gamma"), self._v(X, "X"), self._v(Y, "Y"),
+                                             1 if assembled else 0))
 
     def rc_batch_pcg_state(self):
         it, res = np.zeros(self.n_inst), np.zeros(self.n_inst)

@@ -580,7 +580,7 @@ extern "C" void rc_default_batch_opts(rc_batch_opts* o) {
   o->max_iter = 60;
   o->ls_rounds = 4;
   o->proj_iters = 2;
-  o->proj_max_iter = 10;
+  o->proj_max_iter = 5;
   o->proj_tol = 1e-2;
   o->accept_tol = 1e-6;
   o->c_armijo = 0.01;
@@ -588,6 +588,7 @@ extern "C" void rc_default_batch_opts(rc_batch_opts* o) {
   o->graph = 0;
   o->check_every = 5;
   o->coarse = 1;
+  o->op_assembled = 1;
 }
 
 static rc_status batch_ctx(rc_ctx* c, const char* name) {
@@ -604,7 +605,7 @@ static rc_status batch_opts(const rc_batch_opts* in, rc_batch_opts* o) {
   if (in) *o = *in;
   if (!(o->tol > 0) || o->max_iter < 1 || o->ls_rounds < 1 || o->proj_iters < 0 || o->proj_max_iter < 1 ||
       !(o->proj_tol > 0) || !(o->accept_tol > 0) || !(o->c_armijo > 0) || !(o->tau0 > 0) || o->check_every < 0 ||
-      (o->coarse != 0 && o->coarse != 1)) {
+      (o->coarse != 0 && o->coarse != 1) || (o->op_assembled != 0 && o->op_assembled != 1)) {
     set_error("batch options out of range");
     return RC_ERR_ARG;
   }
@@ -636,6 +637,17 @@ extern "C" rc_status rc_batch_step(rc_ctx* c, double* gamma, const rc_batch_opts
   rc_batch_opts o;
   RC_TRY(batch_opts(opts, &o));
   return batch_step(c, gamma, o, stats_h);
+}
+
+extern "C" rc_status rc_batch_sobolev_apply(rc_ctx* c, const double* gamma, const double* X, double* Y,
+                                            int32_t assembled) {
+  RC_TRY(batch_ctx(c, "rc_batch_sobolev_apply"));
+  RC_TRY(check_ptrs({gamma, X, Y}));
+  if (assembled != 0 && assembled != 1) {
+    set_error("rc_batch_sobolev_apply: assembled must be 0 or 1");
+    return RC_ERR_ARG;
+  }
+  return batch_apply(c, gamma, X, Y, assembled != 0);
 }
 
 extern "C" rc_status rc_batch_pcg_state(rc_ctx* c, double* iters_h, double* res_h) {

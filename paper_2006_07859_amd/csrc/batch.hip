@@ -730,6 +730,109 @@ __global__ __launch_bounds__(64) void k_b_coarse_apply(const double* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// assembled per-instance operator (FP32)
+// ---------------------------------------------------------------------------
+// Entries A_vw (v != w) of every instance's block, from the FP64 geometry with
+// the same entry formula as the precision path (one 16 x 16 tile of the upper
+// triangle per workgroup, mirrored), the diagonal stored as 0.
+template <int EC>
+__global__ __launch_bounds__(256) void k_b_asm_assemble(const int4* __restrict__ items, const int* __restrict__ inst_voff,
+                                                        const long long* __restrict__ aoff,
+                                                        const V4<double>* __restrict__ GA,
+                                                        const V4<double>* __restrict__ GB,
+                                                        const V4<double>* __restrict__ GT,
+                                                        const int2* __restrict__ edges, const int* __restrict__ inc_off,
+                                                        const int* __restrict__ inc,
+                                                        const double* __restrict__ edge_out, float half_expo,
+                                                        float* __restrict__ A) {
+  const int4 it = items[blockIdx.x];
+  const int i = it.x;
+  const int v0 = inst_voff[i], n = inst_voff[i + 1] - v0;
+  const int a = it.y * 16 + threadIdx.x / 16, b = it.z * 16 + threadIdx.x % 16;
+  if (a >= n || b >= n) return;
+  float* Ai = A + aoff[i];
+  if (a == b) {
+    Ai[(size_t)a * n + a] = 0.f;
+    return;
+  }
+  if (b < a) return;  // diagonal tile: the upper half writes both
+  const float val = sobolev_entry<float, EC>(v0 + a, v0 + b, GA, GB, GT, edges, inc_off, inc, edge_out, half_expo);
+  Ai[(size_t)a * n + b] = val;
+  Ai[(size_t)b * n + a] = val;
+}
+
+// Y_v = sum_w A_vw (x_w - x_v) (A 1 = 0, so this is (A X)_v without the
+// diagonal): 16 rows of one instance per workgroup, 4 per wave; the inputs are
+// staged in LDS as FP32 differences to the block's first row, so nearby
+// columns keep their relative accuracy.
+__global__ __launch_bounds__(256) void k_b_asm_apply(const int2* __restrict__ rb_items,
+                                                     const int* __restrict__ inst_voff,
+                                                     const long long* __restrict__ aoff, const float* __restrict__ A,
+                                                     const int* __restrict__ mask, const double* __restrict__ X,
+                                                     double* __restrict__ Y) {
+  __shared__ float xs[3][256];
+  const int2 it = rb_items[blockIdx.x];
+  const int i = it.x;
+  if (mask && !mask[i]) return;
+  const int v0 = inst_voff[i], n = inst_voff[i + 1] - v0, r0 = it.y;
+  const double c0 = X[3 * (v0 + r0)], c1 = X[3 * (v0 + r0) + 1], c2 = X[3 * (v0 + r0) + 2];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  float xv[4][3], acc[4][3];
+  bool rv[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int r = r0 + 4 * wave + j;
+    rv[j] = r < n;
+    const int vr = v0 + (rv[j] ? r : r0);
+    xv[j][0] = (float)(X[3 * vr] - c0);
+    xv[j][1] = (float)(X[3 * vr + 1] - c1);
+    xv[j][2] = (float)(X[3 * vr + 2] - c2);
+    acc[j][0] = acc[j][1] = acc[j][2] = 0.f;
+  }
+  const float* Ab = A + aoff[i];
+  for (int k0 = 0; k0 < n; k0 += 256) {
+    __syncthreads();
+    if (k0 + tid < n) {
+      const int w = v0 + k0 + tid;
+      xs[0][tid] = (float)(X[3 * w] - c0);
+      xs[1][tid] = (float)(X[3 * w + 1] - c1);
+      xs[2][tid] = (float)(X[3 * w + 2] - c2);
+    }
+    __syncthreads();
+    const int cnt = min(256, n - k0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (!rv[j]) continue;
+      const float* Ar = Ab + (size_t)(r0 + 4 * wave + j) * n + k0;
+      for (int k = lane; k < cnt; k += 64) {
+        const float av = Ar[k];
+        acc[j][0] += av * (xs[0][k] - xv[j][0]);
+        acc[j][1] += av * (xs[1][k] - xv[j][1]);
+        acc[j][2] += av * (xs[2][k] - xv[j][2]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float v = acc[j][c];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      acc[j][c] = v;
+    }
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (rv[j]) {
+        const int v = v0 + r0 + 4 * wave + j;
+        Y[3 * v] = (double)acc[j][0];
+        Y[3 * v + 1] = (double)acc[j][1];
+        Y[3 * v + 2] = (double)acc[j][2];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // per-instance PCG scalars and vector updates
 // ---------------------------------------------------------------------------
 __global__ void k_b_fill(double* __restrict__ x, size_t n, double v) {
@@ -1101,7 +1204,8 @@ void batch_free(rc_ctx* c) {
                 B.chain_edges, B.blk_off, B.Minv, B.gj_col, B.x0, B.L0, B.Jv, B.Lv, B.qsum, B.Sinv, B.cq,
                 B.yb, B.yq, B.dvec, B.x, B.r, B.z, B.p, B.q, B.b, B.t, B.trial, B.ghat, B.dE, B.g, B.inc,
                 B.sc, B.ls, B.energy, B.stats, B.phiq, B.phib, B.mask, B.gj_list, B.gj_pre, B.prec_items,
-                B.cedge_loop, B.inst_ceoff, B.cpl_items, B.Wp, B.Wc, B.Ainv, B.rsum, B.cl};
+                B.cedge_loop, B.inst_ceoff, B.cpl_items, B.Wp, B.Wc, B.Ainv, B.rsum, B.cl,
+                B.Aasm, B.aoff, B.asm_items, B.rb_items};
   for (void* p : ps)
     if (p) hipFree(p);
   B = Batch();
@@ -1158,6 +1262,18 @@ static rc_status b_prepare(rc_ctx* c) {
                      B.dvec);
   const double sg = (c->beta - 1.0) / c->alpha - 1.0;
   const double half_expo = 0.5 * (2.0 * sg + 1.0);
+  if (B.use_asm) {  // the solves' operator: every instance's block at gamma
+#define RC_ASM(EC)                                                                                                \
+  hipLaunchKernelGGL((k_b_asm_assemble<EC>), dim3(B.n_asm_items), dim3(256), 0, s, (const int4*)B.asm_items,    \
+                     cv.inst_voff, (const long long*)B.aoff, cv.gd.a, cv.gd.b, cv.gd.t, cv.edges, cv.inc_off, cv.inc, \
+                     cv.edge_out, (float)half_expo, B.Aasm)
+    switch (exp_case(c->alpha, c->beta)) {
+      case kA2B4: RC_ASM(kA2B4); break;
+      case kA2B45: RC_ASM(kA2B45); break;
+      default: RC_ASM(kGeneral); break;
+    }
+#undef RC_ASM
+  }
   const long long tot = (long long)B.blk_total;
   const int nb = (int)((tot + 255) / 256);
 #define RC_BLK(EC)                                                                                                \
@@ -1215,8 +1331,25 @@ static void b_precondition(rc_ctx* c, const double* r, double* z, const int* mas
 }
 
 // q = P Abar p (FP32 operator, geometry of the prepared curve loaded).
-static rc_status b_operator(rc_ctx* c, const double* p, double* q) {
-  RC_TRY(launch_sobolev(c->curve, c->alpha, c->beta, RC_F32, p, q, nullptr, c->stream));
+// Y = Abar X for the instances in mask (all when null): the assembled blocks
+// (use_asm) or the matrix-free FP32 operator, with the geometry of the
+// prepared curve.
+static rc_status b_apply(rc_ctx* c, const double* X, double* Y, const int* mask) {
+  Batch& B = c->batch;
+  if (B.use_asm) {
+    hipLaunchKernelGGL(k_b_asm_apply, dim3(B.n_rb), dim3(256), 0, c->stream, (const int2*)B.rb_items,
+                       c->curve.inst_voff, (const long long*)B.aoff, (const float*)B.Aasm, mask, X, Y);
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+  }
+  c->curve.inst_mask = const_cast<int*>(mask);
+  const rc_status st = launch_sobolev(c->curve, c->alpha, c->beta, RC_F32, X, Y, nullptr, c->stream);
+  c->curve.inst_mask = nullptr;
+  return st;
+}
+
+static rc_status b_operator(rc_ctx* c, const double* p, double* q, const int* mask) {
+  RC_TRY(b_apply(c, p, q, mask));
   b_project(c, q, q);
   return RC_OK;
 }
@@ -1242,10 +1375,7 @@ static rc_status b_pcg(rc_ctx* c, const double* rhs, double* x, double tol, int 
   for (int it = 0; it < max_it; ++it) {
     // only instances still iterating pay for the operator
     hipLaunchKernelGGL(k_b_mask_pcg, gi, bi, 0, s, B.sc, B.n_inst, B.mask);
-    c->curve.inst_mask = B.mask;
-    const rc_status so = b_operator(c, B.p, B.q);
-    c->curve.inst_mask = nullptr;
-    RC_TRY(so);
+    RC_TRY(b_operator(c, B.p, B.q, B.mask));
     hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.p, B.q, vo, B.sc, kBatchScal, (int)S_PQ);
     hipLaunchKernelGGL(k_b_pcg_alpha, gi, bi, 0, s, B.sc, B.n_inst);
     hipLaunchKernelGGL(k_b_xr, gv, bv, 0, s, iv, B.sc, nV, B.p, B.q, x, B.r);
@@ -1266,11 +1396,65 @@ static rc_status b_pcg(rc_ctx* c, const double* rhs, double* x, double tol, int 
   return RC_OK;
 }
 
+// The assembled blocks' storage and work items, allocated on first use
+// (outside any capture).
+static rc_status b_ensure_asm(rc_ctx* c) {
+  Batch& B = c->batch;
+  if (B.Aasm) return RC_OK;
+  const Curve& cv = c->curve;
+  std::vector<long long> off(B.n_inst + 1, 0);
+  std::vector<int4> ait;
+  std::vector<int2> rit;
+  for (int i = 0; i < B.n_inst; ++i) {
+    const long long n = cv.h_inst_voff[i + 1] - cv.h_inst_voff[i];
+    off[i + 1] = off[i] + n * n;
+    const int T = (int)((n + 15) / 16);
+    for (int tr = 0; tr < T; ++tr) {
+      rit.push_back(make_int2(i, 16 * tr));
+      for (int tc = tr; tc < T; ++tc) ait.push_back(make_int4(i, tr, tc, 0));
+    }
+  }
+  if (ait.size() >= (size_t)INT32_MAX || rit.size() >= (size_t)INT32_MAX) {
+    set_error("batch too large for the assembled operator");
+    return RC_ERR_UNSUPPORTED;
+  }
+  B.asm_total = (size_t)off.back();
+  RC_TRY(balloc(&B.Aasm, B.asm_total));
+  RC_TRY(balloc(&B.aoff, B.n_inst + 1));
+  RC_TRY(balloc(&B.asm_items, ait.size()));
+  RC_TRY(balloc(&B.rb_items, rit.size()));
+  RC_HIP(hipMemcpy(B.aoff, off.data(), sizeof(long long) * off.size(), hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(B.asm_items, ait.data(), sizeof(int4) * ait.size(), hipMemcpyHostToDevice));
+  RC_HIP(hipMemcpy(B.rb_items, rit.data(), sizeof(int2) * rit.size(), hipMemcpyHostToDevice));
+  B.n_asm_items = (int)ait.size();
+  B.n_rb = (int)rit.size();
+  return RC_OK;
+}
+
+static rc_status b_choose_operator(rc_ctx* c, bool assembled) {
+  if (assembled) RC_TRY(b_ensure_asm(c));
+  c->batch.use_asm = assembled;
+  return RC_OK;
+}
+
+rc_status batch_apply(rc_ctx* c, const double* gamma, const double* X, double* Y, bool assembled) {
+  if (!c->batch.ready) {
+    set_error("batch constraints not set (rc_batch_set_constraints)");
+    return RC_ERR_ARG;
+  }
+  RC_TRY(b_choose_operator(c, assembled));
+  c->batch.use_coarse = false;
+  RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));
+  if (assembled) RC_TRY(b_prepare(c));
+  return b_apply(c, X, Y, nullptr);
+}
+
 rc_status batch_gradient(rc_ctx* c, const double* gamma, const double* dE, double* g, const rc_batch_opts& o) {
   if (!c->batch.ready) {
     set_error("batch constraints not set (rc_batch_set_constraints)");
     return RC_ERR_ARG;
   }
+  RC_TRY(b_choose_operator(c, o.op_assembled != 0));
   c->batch.use_coarse = c->batch.coarse && o.coarse != 0;
   RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));
   RC_TRY(b_prepare(c));
@@ -1316,10 +1500,7 @@ static rc_status b_step(rc_ctx* c, double* gamma, const rc_batch_opts& o, int ch
                          (const double*)nullptr, -1.0, nV, B.inc);
       // y = (P A P)^+ P A z, increment = z - y (instances still searching)
       hipLaunchKernelGGL(k_b_mask_ls, gi, bi, 0, s, B.ls, B.n_inst, B.mask);
-      cv.inst_mask = B.mask;
-      const rc_status so = launch_sobolev(cv, c->alpha, c->beta, RC_F32, B.inc, B.b, nullptr, s);
-      cv.inst_mask = nullptr;
-      RC_TRY(so);
+      RC_TRY(b_apply(c, B.inc, B.b, B.mask));
       RC_TRY(b_pcg(c, B.b, B.t, o.proj_tol, o.proj_max_iter, 0, B.ls));
       vec_axpby(-1.0, B.t, 1.0, B.inc, n3, s);
       hipLaunchKernelGGL(k_b_add_inc, gv, bv, 0, s, iv, B.ls, nV, B.inc, B.trial);
@@ -1351,13 +1532,14 @@ rc_status batch_step(rc_ctx* c, double* gamma, const rc_batch_opts& o, double* s
     set_error("batch constraints not set (rc_batch_set_constraints)");
     return RC_ERR_ARG;
   }
+  RC_TRY(b_choose_operator(c, o.op_assembled != 0));  // allocations happen here, never inside a capture
   if (o.graph) {
     const rc_batch_opts& k = B.cap_opts;  // field by field: the struct has tail padding
     const bool same_opts = k.tol == o.tol && k.max_iter == o.max_iter && k.ls_rounds == o.ls_rounds &&
                            k.proj_iters == o.proj_iters && k.proj_max_iter == o.proj_max_iter &&
                            k.proj_tol == o.proj_tol && k.accept_tol == o.accept_tol && k.c_armijo == o.c_armijo &&
                            k.tau0 == o.tau0 && k.graph == o.graph && k.check_every == o.check_every &&
-                           k.coarse == o.coarse;
+                           k.coarse == o.coarse && k.op_assembled == o.op_assembled;
     const bool same = B.captured && B.cap_gamma == gamma && same_opts;
     if (!same) {
       if (B.exec) hipGraphExecDestroy(B.exec);

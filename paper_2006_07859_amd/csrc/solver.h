@@ -85,6 +85,14 @@ struct Batch {
   // coarse space of per-loop translations (two-level preconditioner)
   bool coarse = false;      // available (every instance has at most kCoarseMax loops)
   bool use_coarse = false;  // chosen by the options of the current solve
+  // assembled per-instance blocks of Abar (FP32, row-major, diagonal unused)
+  bool use_asm = false;
+  float* Aasm = nullptr;
+  long long* aoff = nullptr;
+  size_t asm_total = 0;
+  int n_asm_items = 0, n_rb = 0;
+  int4* asm_items = nullptr;   // (instance, tile row, tile col >= tile row) of 16 x 16
+  int2* rb_items = nullptr;    // (instance, first of 16 rows)
   int max_loops = 0, n_cpl = 0;
   int *cedge_loop = nullptr, *inst_ceoff = nullptr;
   int2* cpl_items = nullptr;
@@ -183,6 +191,7 @@ rc_status batch_alloc(rc_ctx* c);
 void batch_free(rc_ctx* c);
 rc_status batch_edge_sums(rc_ctx* c, int slot, double* out);
 rc_status batch_set_constraints(rc_ctx* c, const double* gamma_ref);
+rc_status batch_apply(rc_ctx* c, const double* gamma, const double* X, double* Y, bool assembled);
 rc_status batch_gradient(rc_ctx* c, const double* gamma, const double* dE, double* g, const rc_batch_opts& o);
 rc_status batch_step(rc_ctx* c, double* gamma, const rc_batch_opts& o, double* stats_h);
 void batch_invalidate_graph(rc_ctx* c);

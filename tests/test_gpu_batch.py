@@ -95,25 +95,39 @@ def test_obstacle_term_alone(lib):
 
 def test_operator_is_block_diagonal(lib):
     insts = small_batch(n=4, seed=3)
-    banner("batch operator")
+    banner("batch operator: matrix-free and assembled blocks")
     b, g, e, voff = make_batch(insts)
-    X = np.random.default_rng(1).normal(size=g.shape)
+    rng = np.random.default_rng(1)
+    X = rng.normal(size=g.shape)
+    # a smooth input too: the assembled product's difference form must not cancel
+    Xs = np.sin(2.0 * g) + 0.3 * g ** 2
     Y = zeros(len(g), 3)
     b.rc_sobolev_apply(dev(g), dev(X), Y)
-    Y = host(Y)
+    Ys = {}
+    b.rc_batch_set_constraints(dev(g))
+    for assembled in (False, True):
+        for name, inp in (("random", X), ("smooth", Xs)):
+            out = zeros(len(g), 3)
+            b.rc_batch_sobolev_apply(dev(g), dev(inp), out, assembled)
+            Ys[(assembled, name)] = host(out)
     for i, (gi, ei, _) in enumerate(insts):
         A = sum(sobolev.assemble(gi, ei, ALPHA, BETA))
-        ref = A @ X[voff[i]:voff[i + 1]]
-        assert relnorm(Y[voff[i]:voff[i + 1]], ref) < 1e-5
+        sl = slice(voff[i], voff[i + 1])
+        assert relnorm(host(Y)[sl], A @ X[sl]) < 1e-5
+        for (assembled, name), out in Ys.items():
+            ref = A @ (X if name == "random" else Xs)[sl]
+            err = relnorm(out[sl], ref)
+            print(f"  instance {i} assembled={assembled} {name}: rel {err:.1e}")
+            assert err < (1e-5 if name == "random" else 3e-5)
     b.close()
 
 
-@pytest.mark.parametrize("coarse", [1, 0])
-def test_gradient_matches_oracle(lib, coarse):
+@pytest.mark.parametrize("coarse,op", [(1, 1), (0, 1), (1, 0)])
+def test_gradient_matches_oracle(lib, coarse, op):
     from paper_2006_07859_amd import default_batch_opts
 
     insts = small_batch(n=5, seed=5, e_max=400)
-    banner(f"batch projected gradient {len(insts)} instances, coarse space {coarse}")
+    banner(f"batch projected gradient {len(insts)} instances, coarse space {coarse}, assembled operator {op}")
     b, g, e, voff = make_batch(insts)
     gam = dev(g)
     b.rc_batch_set_constraints(gam)
@@ -121,7 +135,8 @@ def test_gradient_matches_oracle(lib, coarse):
     dE = zeros(len(g), 3)
     b.rc_batch_energies(gam, En, dE)
     out = zeros(len(g), 3)
-    b.rc_batch_gradient(gam, dE, out, default_batch_opts(tol=1e-7, max_iter=400, check_every=10, coarse=coarse))
+    b.rc_batch_gradient(gam, dE, out, default_batch_opts(tol=1e-7, max_iter=400, check_every=10, coarse=coarse,
+                                                                 op_assembled=op))
     its, res = b.rc_batch_pcg_state()
     print(f"  iterations {its.astype(int).tolist()} residuals {np.max(res):.1e}")
     out = host(out)
