@@ -747,73 +747,83 @@ __global__ __launch_bounds__(256) void k_b_asm_assemble(const int4* __restrict__
                                                         float* __restrict__ A) {
   const int4 it = items[blockIdx.x];
   const int i = it.x;
-  const int v0 = inst_voff[i], n = inst_voff[i + 1] - v0;
+  const int v0 = inst_voff[i], n = inst_voff[i + 1] - v0, ld = (n + 3) & ~3;
   const int a = it.y * 16 + threadIdx.x / 16, b = it.z * 16 + threadIdx.x % 16;
   if (a >= n || b >= n) return;
   float* Ai = A + aoff[i];
   if (a == b) {
-    Ai[(size_t)a * n + a] = 0.f;
+    Ai[(size_t)a * ld + a] = 0.f;
     return;
   }
   if (b < a) return;  // diagonal tile: the upper half writes both
   const float val = sobolev_entry<float, EC>(v0 + a, v0 + b, GA, GB, GT, edges, inc_off, inc, edge_out, half_expo);
-  Ai[(size_t)a * n + b] = val;
-  Ai[(size_t)b * n + a] = val;
+  Ai[(size_t)a * ld + b] = val;
+  Ai[(size_t)b * ld + a] = val;
 }
 
 // Y_v = sum_w A_vw (x_w - x_v) (A 1 = 0, so this is (A X)_v without the
-// diagonal): 16 rows of one instance per workgroup, 4 per wave; the inputs are
-// staged in LDS as FP32 differences to the block's first row, so nearby
-// columns keep their relative accuracy.
+// diagonal): kAsmRows rows of one instance per workgroup, a quarter per wave.
+// Rows are padded to a multiple of 4 floats (zero padding), so every lane
+// streams 16-byte loads; the inputs are staged in LDS as FP32 differences to
+// the block's first row, so nearby columns keep their relative accuracy.
+constexpr int kAsmRows = 32, kAsmRowsWave = kAsmRows / 4;
 __global__ __launch_bounds__(256) void k_b_asm_apply(const int2* __restrict__ rb_items,
                                                      const int* __restrict__ inst_voff,
                                                      const long long* __restrict__ aoff, const float* __restrict__ A,
                                                      const int* __restrict__ mask, const double* __restrict__ X,
                                                      double* __restrict__ Y) {
-  __shared__ float xs[3][256];
+  __shared__ float4 xs[3][64];  // 256 columns per chunk, as 64 float4 per component
   const int2 it = rb_items[blockIdx.x];
   const int i = it.x;
   if (mask && !mask[i]) return;
-  const int v0 = inst_voff[i], n = inst_voff[i + 1] - v0, r0 = it.y;
+  const int v0 = inst_voff[i], n = inst_voff[i + 1] - v0, ld = (n + 3) & ~3, r0 = it.y;
   const double c0 = X[3 * (v0 + r0)], c1 = X[3 * (v0 + r0) + 1], c2 = X[3 * (v0 + r0) + 2];
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  float xv[4][3], acc[4][3];
-  bool rv[4];
+  float xv[kAsmRowsWave][3], acc[kAsmRowsWave][3];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int r = r0 + 4 * wave + j;
-    rv[j] = r < n;
-    const int vr = v0 + (rv[j] ? r : r0);
-    xv[j][0] = (float)(X[3 * vr] - c0);
-    xv[j][1] = (float)(X[3 * vr + 1] - c1);
-    xv[j][2] = (float)(X[3 * vr + 2] - c2);
+  for (int j = 0; j < kAsmRowsWave; ++j) {
+    const int r = min(r0 + kAsmRowsWave * wave + j, n - 1);
+    xv[j][0] = (float)(X[3 * (v0 + r)] - c0);
+    xv[j][1] = (float)(X[3 * (v0 + r) + 1] - c1);
+    xv[j][2] = (float)(X[3 * (v0 + r) + 2] - c2);
     acc[j][0] = acc[j][1] = acc[j][2] = 0.f;
   }
   const float* Ab = A + aoff[i];
   for (int k0 = 0; k0 < n; k0 += 256) {
     __syncthreads();
-    if (k0 + tid < n) {
-      const int w = v0 + k0 + tid;
-      xs[0][tid] = (float)(X[3 * w] - c0);
-      xs[1][tid] = (float)(X[3 * w + 1] - c1);
-      xs[2][tid] = (float)(X[3 * w + 2] - c2);
+    {
+      const int w = k0 + tid;
+      float* x0 = (float*)&xs[0][0];
+      float* x1 = (float*)&xs[1][0];
+      float* x2 = (float*)&xs[2][0];
+      const bool ok = w < n;
+      x0[tid] = ok ? (float)(X[3 * (v0 + w)] - c0) : 0.f;
+      x1[tid] = ok ? (float)(X[3 * (v0 + w) + 1] - c1) : 0.f;
+      x2[tid] = ok ? (float)(X[3 * (v0 + w) + 2] - c2) : 0.f;
     }
     __syncthreads();
-    const int cnt = min(256, n - k0);
+    const int k = k0 + 4 * lane;  // this lane's 4 columns
+    if (k < n) {
+      const float4 s0 = xs[0][lane], s1 = xs[1][lane], s2 = xs[2][lane];
+      float4 av[kAsmRowsWave];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (!rv[j]) continue;
-      const float* Ar = Ab + (size_t)(r0 + 4 * wave + j) * n + k0;
-      for (int k = lane; k < cnt; k += 64) {
-        const float av = Ar[k];
-        acc[j][0] += av * (xs[0][k] - xv[j][0]);
-        acc[j][1] += av * (xs[1][k] - xv[j][1]);
-        acc[j][2] += av * (xs[2][k] - xv[j][2]);
+      for (int j = 0; j < kAsmRowsWave; ++j) {
+        const int r = min(r0 + kAsmRowsWave * wave + j, n - 1);
+        av[j] = *(const float4*)(Ab + (size_t)r * ld + k);
+      }
+#pragma unroll
+      for (int j = 0; j < kAsmRowsWave; ++j) {
+        acc[j][0] += av[j].x * (s0.x - xv[j][0]) + av[j].y * (s0.y - xv[j][0]) + av[j].z * (s0.z - xv[j][0]) +
+                     av[j].w * (s0.w - xv[j][0]);
+        acc[j][1] += av[j].x * (s1.x - xv[j][1]) + av[j].y * (s1.y - xv[j][1]) + av[j].z * (s1.z - xv[j][1]) +
+                     av[j].w * (s1.w - xv[j][1]);
+        acc[j][2] += av[j].x * (s2.x - xv[j][2]) + av[j].y * (s2.y - xv[j][2]) + av[j].z * (s2.z - xv[j][2]) +
+                     av[j].w * (s2.w - xv[j][2]);
       }
     }
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
+  for (int j = 0; j < kAsmRowsWave; ++j)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       float v = acc[j][c];
@@ -822,13 +832,14 @@ __global__ __launch_bounds__(256) void k_b_asm_apply(const int2* __restrict__ rb
     }
   if (lane == 0) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (rv[j]) {
-        const int v = v0 + r0 + 4 * wave + j;
-        Y[3 * v] = (double)acc[j][0];
-        Y[3 * v + 1] = (double)acc[j][1];
-        Y[3 * v + 2] = (double)acc[j][2];
+    for (int j = 0; j < kAsmRowsWave; ++j) {
+      const int r = r0 + kAsmRowsWave * wave + j;
+      if (r < n) {
+        Y[3 * (v0 + r)] = (double)acc[j][0];
+        Y[3 * (v0 + r) + 1] = (double)acc[j][1];
+        Y[3 * (v0 + r) + 2] = (double)acc[j][2];
       }
+    }
   }
 }
 
@@ -1407,12 +1418,11 @@ static rc_status b_ensure_asm(rc_ctx* c) {
   std::vector<int2> rit;
   for (int i = 0; i < B.n_inst; ++i) {
     const long long n = cv.h_inst_voff[i + 1] - cv.h_inst_voff[i];
-    off[i + 1] = off[i] + n * n;
+    off[i + 1] = off[i] + n * ((n + 3) & ~3LL);  // rows padded to a multiple of 4 floats
     const int T = (int)((n + 15) / 16);
-    for (int tr = 0; tr < T; ++tr) {
-      rit.push_back(make_int2(i, 16 * tr));
+    for (int tr = 0; tr < T; ++tr)
       for (int tc = tr; tc < T; ++tc) ait.push_back(make_int4(i, tr, tc, 0));
-    }
+    for (int r0 = 0; r0 < n; r0 += kAsmRows) rit.push_back(make_int2(i, r0));
   }
   if (ait.size() >= (size_t)INT32_MAX || rit.size() >= (size_t)INT32_MAX) {
     set_error("batch too large for the assembled operator");
@@ -1420,6 +1430,7 @@ static rc_status b_ensure_asm(rc_ctx* c) {
   }
   B.asm_total = (size_t)off.back();
   RC_TRY(balloc(&B.Aasm, B.asm_total));
+  RC_HIP(hipMemset(B.Aasm, 0, sizeof(float) * B.asm_total));  // the row padding stays zero
   RC_TRY(balloc(&B.aoff, B.n_inst + 1));
   RC_TRY(balloc(&B.asm_items, ait.size()));
   RC_TRY(balloc(&B.rb_items, rit.size()));
