@@ -732,9 +732,17 @@ __global__ __launch_bounds__(64) void k_b_coarse_apply(const double* __restrict_
 // ---------------------------------------------------------------------------
 // assembled per-instance operator (FP32)
 // ---------------------------------------------------------------------------
-// Entries A_vw (v != w) of every instance's block, from the FP64 geometry with
-// the same entry formula as the precision path (one 16 x 16 tile of the upper
-// triangle per workgroup, mirrored), the diagonal stored as 0.
+// Entries A_vw (v != w) of every instance's block, from the FP64 geometry
+// (coordinate differences taken in FP64, then rounded), with the terms of the
+// increment tables: over the edges I at v and J at w that share no vertex,
+//   -1/2 s_I(v) s_J(w) rho_IJ <T_I, T_J>  -  l_I l_J rho0_IJ / 16,
+// plus -Wq_K / (2 l_K) + l_K P0_K / 16 when v and w are the two ends of an
+// edge K (s(i1) = -1, s(i2) = +1; rho, rho0 the operator's pair weights).
+// One workgroup per 16 x 16 tile of the upper triangle: the tile's distinct
+// row and column edges are listed once, every distinct edge pair is evaluated
+// once into LDS (about 17 x 17 pairs for loops numbered along themselves,
+// instead of 4 per entry), and each entry sums its four edge pairs from LDS.
+// The diagonal is stored as 0; entries are mirrored.
 template <int EC>
 __global__ __launch_bounds__(256) void k_b_asm_assemble(const int4* __restrict__ items, const int* __restrict__ inst_voff,
                                                         const long long* __restrict__ aoff,
@@ -745,10 +753,97 @@ __global__ __launch_bounds__(256) void k_b_asm_assemble(const int4* __restrict__
                                                         const int* __restrict__ inc,
                                                         const double* __restrict__ edge_out, float half_expo,
                                                         float* __restrict__ A) {
+  __shared__ int slotE[2][16][2];    // [rows / cols][vertex][slot] edge (-1: none)
+  __shared__ float slotS[2][16][2];  // its sign s(v)
+  __shared__ int slotI[2][16][2];    // index in the distinct list
+  __shared__ int list[2][32];
+  __shared__ int nlist[2];
+  __shared__ float G[32][33], H[32][33];
   const int4 it = items[blockIdx.x];
-  const int i = it.x;
+  const int i = it.x, tid = threadIdx.x;
   const int v0 = inst_voff[i], n = inst_voff[i + 1] - v0, ld = (n + 3) & ~3;
-  const int a = it.y * 16 + threadIdx.x / 16, b = it.z * 16 + threadIdx.x % 16;
+  if (tid < 64) {  // slots of the tile's 16 row and 16 column vertices
+    const int side = tid / 32, k = tid % 32, vl = k / 2, sl = k % 2;
+    const int loc = (side == 0 ? it.y : it.z) * 16 + vl;
+    int e = -1;
+    float sg = 0.f;
+    if (loc < n) {
+      const int v = v0 + loc;
+      const int kk = inc_off[v] + sl;
+      if (kk < inc_off[v + 1]) {
+        e = inc[kk] >> 1;
+        sg = (inc[kk] & 1) ? 1.f : -1.f;
+      }
+    }
+    slotE[side][vl][sl] = e;
+    slotS[side][vl][sl] = sg;
+  }
+  __syncthreads();
+  // distinct edges of each side in slot order: lanes 0-31 rows, 32-63 columns
+  // of wave 0; a slot is new if no earlier slot of its side has its edge, its
+  // index is the number of new slots before it (ballot + popcount)
+  int firstpos = -1;
+  if (tid < 64) {
+    const int side = tid / 32, k = tid % 32;
+    const int e = slotE[side][k / 2][k % 2];
+    bool fresh = e >= 0;
+    for (int q = 0; q < k && fresh; ++q)
+      if (slotE[side][q / 2][q % 2] == e) {
+        fresh = false;
+        firstpos = q;
+      }
+    const unsigned long long bal = __ballot(fresh);
+    const unsigned int sm = (unsigned int)(bal >> (32 * side));
+    const int idx = __popc(sm & ((1u << k) - 1u));
+    if (fresh) {
+      list[side][idx] = e;
+      slotI[side][k / 2][k % 2] = idx;
+    } else if (e < 0) {
+      slotI[side][k / 2][k % 2] = -1;
+    }
+    if (k == 0) nlist[side] = __popc(sm);
+  }
+  __syncthreads();
+  if (firstpos >= 0) {  // a repeated edge takes the index of its first slot
+    const int side = tid / 32, k = tid % 32;
+    slotI[side][k / 2][k % 2] = slotI[side][firstpos / 2][firstpos % 2];
+  }
+  __syncthreads();
+  const int nr = nlist[0], nc = nlist[1];
+  for (int p = tid; p < nr * nc; p += 256) {
+    const int a = p / nc, b = p % nc;
+    const int I = list[0][a], J = list[1][b];
+    float g = 0.f, h = 0.f;
+    const int2 ei = edges[I], ej = edges[J];
+    if (I != J && ei.x != ej.x && ei.x != ej.y && ei.y != ej.x && ei.y != ej.y) {
+      const V4<double> ia = GA[I], ib = GB[I], td = GT[I], ja = GA[J], jb = GB[J], tjd = GT[J];
+      const float tix = (float)td.x, tiy = (float)td.y, tiz = (float)td.z;
+      const float tjx = (float)tjd.x, tjy = (float)tjd.y, tjz = (float)tjd.z;
+      float rho = 0.f, rho0 = 0.f;
+      const V4<double>* P[2] = {&ia, &ib};
+      const V4<double>* Q[2] = {&ja, &jb};
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const float dx = (float)(P[x]->x - Q[y]->x), dy = (float)(P[x]->y - Q[y]->y),
+                      dz = (float)(P[x]->z - Q[y]->z);
+          const float r2 = dx * dx + dy * dy + dz * dz;
+          const float rs = f_rsq<float>(r2), ri = rs * rs;
+          const float pw = pow_sigma<EC, float>(r2, rs, ri, half_expo);
+          rho += pw;
+          rho0 += pw * (cross_norm2<float>(tix, tiy, tiz, dx, dy, dz) + cross_norm2<float>(tjx, tjy, tjz, dx, dy, dz)) *
+                  ri * ri;
+        }
+      g = rho * (tix * tjx + tiy * tjy + tiz * tjz);
+      h = (float)ia.w * (float)ja.w * rho0;
+    }
+    G[a][b] = g;
+    H[a][b] = h;
+  }
+  __syncthreads();
+  const int ty = tid / 16, tx = tid % 16;
+  const int a = it.y * 16 + ty, b = it.z * 16 + tx;
   if (a >= n || b >= n) return;
   float* Ai = A + aoff[i];
   if (a == b) {
@@ -756,9 +851,29 @@ __global__ __launch_bounds__(256) void k_b_asm_assemble(const int4* __restrict__
     return;
   }
   if (b < a) return;  // diagonal tile: the upper half writes both
-  const float val = sobolev_entry<float, EC>(v0 + a, v0 + b, GA, GB, GT, edges, inc_off, inc, edge_out, half_expo);
-  Ai[(size_t)a * ld + b] = val;
-  Ai[(size_t)b * ld + a] = val;
+  float acc = 0.f;
+#pragma unroll
+  for (int su = 0; su < 2; ++su) {
+    const int I = slotE[0][ty][su];
+    if (I < 0) continue;
+    const int ia = slotI[0][ty][su];
+    const float si = slotS[0][ty][su];
+#pragma unroll
+    for (int sw = 0; sw < 2; ++sw) {
+      const int J = slotE[1][tx][sw];
+      if (J < 0) continue;
+      if (I == J) {  // v and w are the two ends of edge I
+        const double* o = edge_out + 8 * (size_t)I;  // (Wq, P0) in slots 0, 1
+        const double l = GA[I].w;
+        acc += (float)(-o[0] / (2.0 * l) + l * o[1] / 16.0);
+        continue;
+      }
+      const int jb = slotI[1][tx][sw];
+      acc += -0.5f * si * slotS[1][tx][sw] * G[ia][jb] - 0.0625f * H[ia][jb];
+    }
+  }
+  Ai[(size_t)a * ld + b] = acc;
+  Ai[(size_t)b * ld + a] = acc;
 }
 
 // Y_v = sum_w A_vw (x_w - x_v) (A 1 = 0, so this is (A X)_v without the
