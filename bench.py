@@ -550,6 +550,19 @@ def bench_batch(args):
     T = (time.perf_counter() - t1) / args.steps
     st = b.rc_batch_step(gamma, default_batch_opts(graph=1), stats=True)  # one more step, for its statistics
     ok = st[:, 5] == 0
+    # the solves' operator alone: full-batch products with the assembled blocks, timed with HIP events
+    Xr = dev(np.random.default_rng(2).normal(size=g.shape))
+    Yr = torch.zeros_like(Xr)
+    b.rc_batch_sobolev_apply(gamma, Xr, Yr, True)  # assembles at gamma
+    b.rc_profile_enable(True)
+    for _ in range(10):
+        b.rc_batch_sobolev_apply(gamma, Xr, Yr, True)
+    asm_ms, asm_n = b.rc_profile_read(5)
+    b.rc_profile_enable(False)
+    sizes = np.diff(np.asarray(voff)).astype(np.int64)
+    asm_bytes = int((sizes * sizes).sum() * 4)  # every FP32 entry once
+    asm_avg = asm_ms / max(asm_n, 1) * 1e-3
+    asm_gbs = asm_bytes / asm_avg / 1e9
     achieved = FLOPS_PER_PAIR_TPE * P / tpe_avg / 1e12
     big = int(np.argmax(np.diff(voff)))
     out = {
@@ -567,8 +580,8 @@ def bench_batch(args):
         "data": "synthetic",
         "config": {"workload": f"512 packing instances ({len(e)} edges, 8-32 circles each, 200-8,000 edges per "
                                f"instance), (alpha,beta)=(3,6), sphere obstacle, barycenter + per-loop length "
-                               f"constraints; step = one captured hipGraph (energy, gradient by loop-block PCG, "
-                               f"per-instance line search)", "edges": int(len(e)), "ordered_pairs": int(P)},
+                               f"constraints; step = one captured hipGraph (energy, gradient by PCG on the "
+                               f"assembled FP32 blocks with the two-level preconditioner, per-instance line search)", "edges": int(len(e)), "ordered_pairs": int(P)},
         "batch_steps_per_s": 1.0 / T,
         "energy_differential_ms": t_eval * 1e3,
         "tiling": tune,
@@ -576,6 +589,11 @@ def bench_batch(args):
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
                      "kernel": "k_tpe_items<float> (persistent, energy+differential)", "launches": tpe_n,
                      "avg_launch_ms": round(tpe_avg * 1e3, 4)},
+        "roofline_step_operator": {"bound": "hbm", "achieved": round(asm_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                   "frac": round(asm_gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                                   "kernel": "k_b_asm_apply (assembled per-instance FP32 blocks, whole batch)",
+                                   "launches": asm_n, "avg_launch_ms": round(asm_avg * 1e3, 4),
+                                   "bytes_per_launch": asm_bytes},
         "step_stats": {"accepted": int(ok.sum()), "pcg_iterations_mean": float(st[:, 3].mean()),
                        "pcg_iterations_max": float(st[:, 3].max()),
                        "energy_drop_mean": float(np.mean((st[ok, 0] - st[ok, 1]) / st[ok, 0]))},

@@ -442,7 +442,8 @@ rc_status rc_learned_train_step(rc_ctx* ctx, const double* gamma, const double* 
  * which = 0: the energy + differential pair kernel, 1: the FP32 operator pair
  * kernel on the finest level (coarse multigrid levels are not timed), 2: the
  * 16-bit assembled product kernel on the finest level, 3: the FP32 assembled
- * product kernel, 4: the FP64 operator pair kernel on the finest level. */
+ * product kernel, 4: the FP64 operator pair kernel on the finest level, 5: the
+ * batch's assembled per-instance product (not recorded inside a captured step). */
 rc_status rc_profile_enable(rc_ctx* ctx, int32_t enable);
 rc_status rc_profile_read(rc_ctx* ctx, int32_t which, double* total_ms, int32_t* launches);
 

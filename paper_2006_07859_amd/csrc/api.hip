@@ -429,15 +429,16 @@ extern "C" rc_status rc_profile_enable(rc_ctx* c, int32_t enable) {
 extern "C" rc_status rc_profile_read(rc_ctx* c, int32_t which, double* total_ms, int32_t* launches) {
   RC_TRY(check_ctx(c));
   RC_TRY(check_ptrs({total_ms, launches}));
-  if (which < 0 || which > 4) {
+  if (which < 0 || which > 5) {
     set_error("rc_profile_read: which must be 0 (energy+differential pairs), 1 (FP32 operator pairs), 2 "
-              "(assembled 16-bit product), 3 (assembled FP32 product) or 4 (FP64 operator pairs)");
+              "(assembled 16-bit product), 3 (assembled FP32 product), 4 (FP64 operator pairs) or 5 (batch "
+              "assembled product)");
     return RC_ERR_ARG;
   }
   RC_HIP(hipStreamSynchronize(c->stream));
   const std::vector<hipEvent_t>& v =
       which == 0 ? c->timer.tpe : which == 1 ? c->timer.sob : which == 2 ? c->timer.lowp
-                                : which == 3 ? c->timer.asm32 : c->timer.sob64;
+                                : which == 3 ? c->timer.asm32 : which == 4 ? c->timer.sob64 : c->timer.basm;
   double tot = 0.0;
   for (size_t i = 0; i + 1 < v.size(); i += 2) {
     float ms = 0.f;

@@ -498,29 +498,55 @@ __global__ __launch_bounds__(256) void k_gj_update(int k, const int* __restrict_
   }
 }
 
-// z_v = sum_{w in loop(v)} Minv[v][w] r_w: each workgroup takes 16 rows of one
-// loop (work items (loop, first row)), a wave per row, lanes along the row.
+// z_v = sum_{w in loop(v)} Minv[v][w] r_w + (coarse value of the loop): each
+// workgroup takes 64 rows of one loop (work items (loop, first row)), a wave
+// per row, lanes along the row; the loop's r is staged in LDS, the blocks are
+// read from their FP32 copy.
+constexpr int kPrecRows = 64;    // rows of one loop block per workgroup
+constexpr int kPrecLds = 1536;   // loops up to this size stage their r in LDS
 __global__ __launch_bounds__(256) void k_b_prec(const int2* __restrict__ prec_items,
                                                 const int* __restrict__ chain_vert, const int* __restrict__ chain_voff,
-                                                const long long* __restrict__ blk_off, const double* __restrict__ Minv,
+                                                const long long* __restrict__ blk_off, const float* __restrict__ Minv,
                                                 const int* __restrict__ chain_inst, const int* __restrict__ mask,
                                                 const double* __restrict__ cl, const double* __restrict__ r,
                                                 double* __restrict__ z) {
+  __shared__ double rs[3][kPrecLds];
   const int2 it = prec_items[blockIdx.x];
   const int q = it.x;
   if (mask && !mask[chain_inst[q]]) return;  // instance no longer iterating: z is not used
   const int m = chain_voff[q + 1] - chain_voff[q];
   const int* vs = chain_vert + chain_voff[q];
-  const double* M = Minv + blk_off[q];
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  for (int a = it.y + wave; a < min(m, it.y + 16); a += 4) {
-    double s0 = 0, s1 = 0, s2 = 0;
-    for (int b = lane; b < m; b += 64) {
-      const double mv = M[(size_t)a * m + b];
+  const float* M = Minv + blk_off[q];
+  const bool lds = m <= kPrecLds;
+  if (lds) {
+    for (int b = threadIdx.x; b < m; b += 256) {
       const int w = vs[b];
-      s0 += mv * r[3 * w];
-      s1 += mv * r[3 * w + 1];
-      s2 += mv * r[3 * w + 2];
+      rs[0][b] = r[3 * w];
+      rs[1][b] = r[3 * w + 1];
+      rs[2][b] = r[3 * w + 2];
+    }
+    __syncthreads();
+  }
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const double c0 = cl ? cl[3 * q] : 0.0, c1 = cl ? cl[3 * q + 1] : 0.0, c2 = cl ? cl[3 * q + 2] : 0.0;
+  for (int a = it.y + wave; a < min(m, it.y + kPrecRows); a += 4) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    const float* Ma = M + (size_t)a * m;
+    if (lds) {
+      for (int b = lane; b < m; b += 64) {
+        const double mv = (double)Ma[b];
+        s0 += mv * rs[0][b];
+        s1 += mv * rs[1][b];
+        s2 += mv * rs[2][b];
+      }
+    } else {
+      for (int b = lane; b < m; b += 64) {
+        const double mv = (double)Ma[b];
+        const int w = vs[b];
+        s0 += mv * r[3 * w];
+        s1 += mv * r[3 * w + 1];
+        s2 += mv * r[3 * w + 2];
+      }
     }
     for (int o = 32; o > 0; o >>= 1) {
       s0 += __shfl_down(s0, o);
@@ -529,12 +555,17 @@ __global__ __launch_bounds__(256) void k_b_prec(const int2* __restrict__ prec_it
     }
     if (lane == 0) {
       const int v = vs[a];
-      const double c0 = cl ? cl[3 * q] : 0.0, c1 = cl ? cl[3 * q + 1] : 0.0, c2 = cl ? cl[3 * q + 2] : 0.0;
       z[3 * v] = s0 + c0;  // + the coarse correction of the loop
       z[3 * v + 1] = s1 + c1;
       z[3 * v + 2] = s2 + c2;
     }
   }
+}
+
+// FP32 copy of the inverted loop blocks (the preconditioner reads it).
+__global__ void k_b_minv_f32(const double* __restrict__ Minv, size_t n, float* __restrict__ out) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+    out[k] = (float)Minv[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -1228,6 +1259,7 @@ rc_status batch_alloc(rc_ctx* c) {
   RC_HIP(hipMemcpy(B.blk_off, boff.data(), sizeof(long long) * (B.nq + 1), hipMemcpyHostToDevice));
   const size_t n3 = 3 * (size_t)nV;
   RC_TRY(balloc(&B.Minv, B.blk_total));
+  RC_TRY(balloc(&B.MinvF, B.blk_total));
   RC_TRY(balloc(&B.gj_col, (size_t)kGT * nV));
   // tile steps of the blocked inversion: the blocks that have tile k, with
   // prefix sums of their tile counts; work items of the block products
@@ -1263,7 +1295,7 @@ rc_status batch_alloc(rc_ctx* c) {
     RC_HIP(hipMemcpy(B.gj_pre, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice));
     std::vector<int2> pit;
     for (int q = 0; q < B.nq; ++q)
-      for (int r0 = 0; r0 < cvoff[q + 1] - cvoff[q]; r0 += 16) pit.push_back(make_int2(q, r0));
+      for (int r0 = 0; r0 < cvoff[q + 1] - cvoff[q]; r0 += kPrecRows) pit.push_back(make_int2(q, r0));
     B.n_prec = (int)pit.size();
     RC_TRY(balloc(&B.prec_items, pit.size()));
     RC_HIP(hipMemcpy(B.prec_items, pit.data(), sizeof(int2) * pit.size(), hipMemcpyHostToDevice));
@@ -1331,7 +1363,7 @@ void batch_free(rc_ctx* c) {
                 B.yb, B.yq, B.dvec, B.x, B.r, B.z, B.p, B.q, B.b, B.t, B.trial, B.ghat, B.dE, B.g, B.inc,
                 B.sc, B.ls, B.energy, B.stats, B.phiq, B.phib, B.mask, B.gj_list, B.gj_pre, B.prec_items,
                 B.cedge_loop, B.inst_ceoff, B.cpl_items, B.Wp, B.Wc, B.Ainv, B.rsum, B.cl,
-                B.Aasm, B.aoff, B.asm_items, B.rb_items};
+                B.Aasm, B.aoff, B.asm_items, B.rb_items, B.MinvF};
   for (void* p : ps)
     if (p) hipFree(p);
   B = Batch();
@@ -1419,6 +1451,7 @@ static rc_status b_prepare(rc_ctx* c) {
     hipLaunchKernelGGL(k_gj_update, dim3(B.h_gj_tiles[k]), dim3(256), 0, s, k, B.gj_list + off, B.gj_pre + off, nact,
                        B.chain_voff, B.blk_off, B.Minv, (const double*)B.gj_col);
   }
+  hipLaunchKernelGGL(k_b_minv_f32, dim3(4096), dim3(256), 0, s, (const double*)B.Minv, B.blk_total, B.MinvF);
   if (B.use_coarse) {  // loop couplings (FP32 pair sums, FP32 geometry of gamma) and the coarse inverses
 #define RC_CPL(EC)                                                                                             \
   hipLaunchKernelGGL((k_b_coupling<EC>), dim3(B.n_cpl), dim3(256), 0, s, cv.gf.a, cv.gf.b, cv.gf.t, B.chain_edges, \
@@ -1451,7 +1484,8 @@ static void b_precondition(rc_ctx* c, const double* r, double* z, const int* mas
                        B.max_loops, mask, (const double*)B.rsum, B.cl);
   }
   hipLaunchKernelGGL(k_b_prec, dim3(B.n_prec), dim3(256), 0, s, B.prec_items, B.chain_vert, B.chain_voff,
-                     B.blk_off, B.Minv, (const int*)B.chain_inst, mask, B.use_coarse ? (const double*)B.cl : nullptr,
+                     B.blk_off, (const float*)B.MinvF, (const int*)B.chain_inst, mask,
+                     B.use_coarse ? (const double*)B.cl : nullptr,
                      r, z);
   b_project(c, z, z);
 }
@@ -1463,8 +1497,11 @@ static void b_precondition(rc_ctx* c, const double* r, double* z, const int* mas
 static rc_status b_apply(rc_ctx* c, const double* X, double* Y, const int* mask) {
   Batch& B = c->batch;
   if (B.use_asm) {
+    KernelTimer* t = c->curve.timer && c->curve.timer->on ? c->curve.timer : nullptr;  // null while capturing
+    if (t) t->mark(t->basm, c->stream);
     hipLaunchKernelGGL(k_b_asm_apply, dim3(B.n_rb), dim3(256), 0, c->stream, (const int2*)B.rb_items,
                        c->curve.inst_voff, (const long long*)B.aoff, (const float*)B.Aasm, mask, X, Y);
+    if (t) t->mark(t->basm, c->stream);
     RC_HIP(hipGetLastError());
     return RC_OK;
   }

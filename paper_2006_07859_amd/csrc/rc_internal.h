@@ -80,7 +80,7 @@ constexpr int kBand = 32;
 // Optional HIP-event timing of the pair kernels (enabled per context).
 struct KernelTimer {
   bool on = false;
-  std::vector<hipEvent_t> tpe, sob, lowp, asm32, sob64;  // start/stop pairs, in launch order
+  std::vector<hipEvent_t> tpe, sob, lowp, asm32, sob64, basm;  // start/stop pairs, in launch order
   void mark(std::vector<hipEvent_t>& v, hipStream_t s) {
     if (!on) return;
     hipEvent_t e;
@@ -94,7 +94,9 @@ struct KernelTimer {
     for (hipEvent_t e : lowp) hipEventDestroy(e);
     for (hipEvent_t e : asm32) hipEventDestroy(e);
     for (hipEvent_t e : sob64) hipEventDestroy(e);
+    for (hipEvent_t e : basm) hipEventDestroy(e);
     sob64.clear();
+    basm.clear();
     tpe.clear();
     sob.clear();
     lowp.clear();

@@ -70,6 +70,7 @@ struct Batch {
   size_t blk_total = 0;
   int max_chain = 0;
   double *Minv = nullptr, *gj_col = nullptr;
+  float* MinvF = nullptr;          // FP32 copy of the inverted loop blocks (the preconditioner's operand)
   double *x0 = nullptr, *L0 = nullptr;
   double *Jv = nullptr, *Lv = nullptr, *qsum = nullptr, *Sinv = nullptr, *cq = nullptr, *yb = nullptr, *yq = nullptr;
   double *dvec = nullptr;
