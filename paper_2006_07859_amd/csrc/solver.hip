@@ -673,8 +673,11 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
                                   c->alpha, c->beta, st.diag, s));
     else
       RC_TRY(launch_sobolev(cv, c->alpha, c->beta, prec, st.pw, st.t, st.diag, s));
-    // lambda_max of P D^-1 P A P by power iteration, warm-started from the last call's vector
-    double nrm = 0.0;
+    // lambda_max of P D^-1 P A P by power iteration, warm-started from the last call's vector:
+    // at most 12 iterations, stopping once the estimate moves by less than 1 % after at least 3
+    // (warm start) or 8 (first call) of them
+    const int min_it = st.lmax > 0.0 ? 3 : 8;
+    double nrm = 0.0, prev = 0.0;
     for (int it = 0; it < 12; ++it) {
       cons_project(c, cv, K, st.pw, st.pw);
       RC_TRY(apply_level(c, l, st.pw, st.t));
@@ -690,6 +693,8 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
         return RC_ERR_SINGULAR;
       }
       vec_axpby(1.0 / nrm, st.d, 0.0, st.pw, 3 * n, s);
+      if (it + 1 >= min_it && std::fabs(nrm - prev) < 0.01 * nrm) break;
+      prev = nrm;
     }
     st.lmax = 1.1 * nrm;
     if (trace_on()) fprintf(stderr, "[rc mg] level %d n %d lmax %.6e\n", l, n, nrm);
