@@ -8,14 +8,25 @@
 namespace rc {
 
 // ---------------------------------------------------------------------------
-// math helpers: hardware transcendentals in FP32, library ones in FP64
+// math helpers: hardware transcendentals in FP32; in FP64 the hardware
+// reciprocal square root refined by Newton-Raphson, library exp2/log2
 // ---------------------------------------------------------------------------
 template <typename R> __device__ __forceinline__ R f_rsq(R x);
 template <> __device__ __forceinline__ float f_rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-template <> __device__ __forceinline__ double f_rsq<double>(double x) { return rsqrt(x); }
+// 1/sqrt(x) for finite x > 0 (squared distances here): the hardware estimate
+// and two Newton-Raphson steps for f(y) = 1/y^2 - x, y <- y + y (1 - x y^2) / 2,
+// each roughly squaring the relative error.  No range handling: x = 0 or
+// x = inf give NaN (the pair sums would be infinite there anyway).
+template <> __device__ __forceinline__ double f_rsq<double>(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
 template <typename R> __device__ __forceinline__ R f_sqrt(R x);
 template <> __device__ __forceinline__ float f_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
-template <> __device__ __forceinline__ double f_sqrt<double>(double x) { return sqrt(x); }
+// sqrt(x) = x / sqrt(x) for x > 0, and 0 for x = 0.
+template <> __device__ __forceinline__ double f_sqrt<double>(double x) { return x > 0.0 ? x * f_rsq<double>(x) : 0.0; }
 template <typename R> __device__ __forceinline__ R f_exp2(R x);
 template <> __device__ __forceinline__ float f_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
 template <> __device__ __forceinline__ double f_exp2<double>(double x) { return exp2(x); }
