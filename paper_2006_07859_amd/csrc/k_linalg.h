@@ -40,13 +40,19 @@ void cons_border_solve(const double* Sinv, const double* wb, const double* dots,
 void cons_sub_Zy(const double* Z, const double* yb, int nb, int np, double* yp, hipStream_t s);
 // P x in three launches when nb <= kProjMaxBorder (in and out may alias:
 // every output entry is written by the last launch from its own input
-// entry).  part: device double [64 * 2 * kProjMaxBorder]; wp, yp: [np]; yb: [nb].
+// entry).  part: device double [64 * 2 * kProjMaxBorder]; yb: [nb].  The
+// factors lo_ch, uinv_ch, tc_ch (from tridiag_chunk_copy) and the work vectors
+// wp_ch, yp_ch are in the solve's chunk-transposed order, tri_chunk_size(np)
+// entries each.
 constexpr int kProjMaxBorder = 8;
 void cons_project_fused(const double* geo, const int2* edges, const int* path_edge, int np, const double* rows,
-                        int nb, const double* Z, const double* Sinv, const double* lo, const double* uinv,
-                        const double* tc, const int* inc_off, const int* inc, const int* edge_path_row, int nV,
-                        const double* in, double* out, double* part, double* wp, double* yp, double* yb,
+                        int nb, const double* Z, const double* Sinv, const double* lo_ch, const double* uinv_ch,
+                        const double* tc_ch, const int* inc_off, const int* inc, const int* edge_path_row, int nV,
+                        const double* in, double* out, double* part, double* wp_ch, double* yp_ch, double* yb,
                         hipStream_t s);
+int tri_chunk_size(int n);
+void tridiag_chunk_copy(const double* lo, const double* uinv, const double* c, int n, double* lo_ch,
+                        double* uinv_ch, double* c_ch, hipStream_t s);
 
 // dense direct path
 void dense_build_H(const double* A, const double* CtC, int nV, double* H, hipStream_t s);

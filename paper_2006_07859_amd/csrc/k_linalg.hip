@@ -296,7 +296,7 @@ void dense_gemv(const double* A, const double* x, double* y, int n, hipStream_t 
 // Rows k < n: a[k] y[k-1] + d[k] y[k] + c[k] y[k+1] = b[k] with a[0] = c[n-1] = 0
 // (zero couplings also separate independent segments).  The factorisation
 // l[k] = a[k] / u[k-1], u[k] = d[k] - l[k] c[k-1] is a nonlinear recurrence and
-// runs in one thread once per system; it stores l and 1/u.  A solve is two
+// runs in one wave once per system; it stores l and 1/u.  A solve is two
 // first-order linear recurrences, forward  z[k] = b[k] - l[k] z[k-1]  and
 // backward  y[k] = (z[k] - c[k] y[k+1]) / u[k].  Each is an affine map per row;
 // one workgroup composes the maps of contiguous chunks per thread (held in
@@ -305,22 +305,45 @@ void dense_gemv(const double* A, const double* x, double* y, int n, hipStream_t 
 // then replays its chunk.
 // The system is symmetric positive definite (a constraint Gram matrix), so
 // the factorisation needs no pivoting.
-__global__ void k_tridiag_factor(const double* __restrict__ a, const double* __restrict__ d,
-                                 const double* __restrict__ c, int n, double* __restrict__ lo,
-                                 double* __restrict__ uinv, int* __restrict__ info) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ double readlane_f64(double v, int j) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, j);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), j);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// One wave: the coefficients of 64 rows at a time are loaded coalesced and
+// handed to the recurrence by lane reads; lane j keeps row j's factors.
+__global__ __launch_bounds__(64) void k_tridiag_factor(const double* __restrict__ a, const double* __restrict__ d,
+                                                       const double* __restrict__ c, int n, double* __restrict__ lo,
+                                                       double* __restrict__ uinv, int* __restrict__ info) {
+  if (blockIdx.x != 0) return;
+  const int lane = threadIdx.x;
   double u_prev = 1.0, c_prev = 0.0;
   int bad = 0;
-  for (int k = 0; k < n; ++k) {
-    const double l = (k == 0) ? 0.0 : a[k] / u_prev;
-    const double u = d[k] - l * c_prev;
-    if (!(u > 0.0)) bad = k + 1;
-    lo[k] = l;
-    uinv[k] = 1.0 / u;
-    u_prev = u;
-    c_prev = c[k];
+  for (int k0 = 0; k0 < n; k0 += 64) {
+    const int k = k0 + lane;
+    const double ak = k < n ? a[k] : 0.0, dk = k < n ? d[k] : 1.0, ck = k < n ? c[k] : 0.0;
+    const int cnt = min(64, n - k0);
+    double my_l = 0.0, my_ui = 0.0;
+    for (int j = 0; j < cnt; ++j) {
+      const double aj = readlane_f64(ak, j), dj = readlane_f64(dk, j);
+      const double l = (k0 + j == 0) ? 0.0 : aj / u_prev;
+      const double u = dj - l * c_prev;
+      if (!(u > 0.0)) bad = k0 + j + 1;
+      if (lane == j) {
+        my_l = l;
+        my_ui = 1.0 / u;
+      }
+      u_prev = u;
+      c_prev = readlane_f64(ck, j);
+    }
+    if (k < n) {
+      lo[k] = my_l;
+      uinv[k] = my_ui;
+    }
   }
-  info[0] = bad;
+  if (lane == 0) info[0] = bad;
 }
 
 constexpr int kTriThreads = 1024;
@@ -360,15 +383,25 @@ __device__ __forceinline__ void scan_compose(double& a, double& b, bool rev, dou
     eb = 0.0;
   }
   __syncthreads();
-  if (t == 0) {  // exclusive scan of the wave totals in scan order, in place
-    double ca = 1.0, cb = 0.0;
-    for (int k = 0; k < kTriWaves; ++k) {
-      const int ww = rev ? kTriWaves - 1 - k : k;
-      const double ta = wa[ww], tb = wb[ww];
-      wa[ww] = ca;
-      wb[ww] = cb;
-      cb = ta * cb + tb;
-      ca = ta * ca;
+  if (w == 0) {  // exclusive scan of the wave totals in scan order, in place: lane q holds the q-th total
+    const int ww = rev ? kTriWaves - 1 - lane : lane;
+    double ta = lane < kTriWaves ? wa[ww] : 1.0, tb = lane < kTriWaves ? wb[ww] : 0.0;
+#pragma unroll
+    for (int off = 1; off < kTriWaves; off <<= 1) {
+      const double pa = __shfl_up(ta, off, 64), pb = __shfl_up(tb, off, 64);
+      if (lane >= off) {
+        tb = ta * pb + tb;
+        ta = ta * pa;
+      }
+    }
+    double xa = __shfl_up(ta, 1, 64), xb = __shfl_up(tb, 1, 64);
+    if (lane == 0) {
+      xa = 1.0;
+      xb = 0.0;
+    }
+    if (lane < kTriWaves) {
+      wa[ww] = xa;
+      wb[ww] = xb;
     }
   }
   __syncthreads();
@@ -380,12 +413,21 @@ __device__ __forceinline__ void scan_compose(double& a, double& b, bool rev, dou
 
 // y = K^-1 b for the factorised tridiagonal K, by one workgroup of
 // kTriThreads threads (every thread must call it); wa, wb: LDS [kTriWaves].
+// Thread t owns rows t m .. t m + m - 1 (m = ceil(n / kTriThreads)).  With
+// Chunked, every array is stored chunk-transposed: row t m + j at position
+// j kTriThreads + t (tri_chunk_pos), so that the j-th row of all threads is one
+// coalesced load; otherwise arrays are in row order.
+__host__ __device__ __forceinline__ int tri_chunk_pos(int k, int m) { return (k % m) * kTriThreads + k / m; }
+
+template <bool Chunked>
 __device__ __forceinline__ void tridiag_solve_wg(const double* __restrict__ lo, const double* __restrict__ uinv,
                                                  const double* __restrict__ c, const double* __restrict__ b,
                                                  double* __restrict__ y, int n, double* wa, double* wb) {
   const int t = threadIdx.x;
   const int m = (n + kTriThreads - 1) / kTriThreads;
   const int k0 = min(n, t * m), k1 = min(n, k0 + m), cnt = k1 - k0;
+  // position of the thread's j-th row
+  auto at = [&](int j) { return Chunked ? j * kTriThreads + t : k0 + j; };
   const bool reg = m <= kTriReg;
   double rl[kTriReg], rz[kTriReg];
   // forward: z[k] = -l[k] z[k-1] + b[k]; chunk composite z_out = A z_in + B
@@ -393,8 +435,8 @@ __device__ __forceinline__ void tridiag_solve_wg(const double* __restrict__ lo, 
   if (reg) {
 #pragma unroll
     for (int j = 0; j < kTriReg; ++j) {
-      rl[j] = j < cnt ? lo[k0 + j] : 0.0;
-      rz[j] = j < cnt ? b[k0 + j] : 0.0;
+      rl[j] = j < cnt ? lo[at(j)] : 0.0;
+      rz[j] = j < cnt ? b[at(j)] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < kTriReg; ++j)
@@ -403,10 +445,10 @@ __device__ __forceinline__ void tridiag_solve_wg(const double* __restrict__ lo, 
         B = -rl[j] * B + rz[j];
       }
   } else {
-    for (int k = k0; k < k1; ++k) {
-      const double l = lo[k];
+    for (int j = 0; j < cnt; ++j) {
+      const double l = lo[at(j)];
       A = -l * A;
-      B = -l * B + b[k];
+      B = -l * B + b[at(j)];
     }
   }
   scan_compose(A, B, false, wa, wb);
@@ -419,9 +461,9 @@ __device__ __forceinline__ void tridiag_solve_wg(const double* __restrict__ lo, 
         rz[j] = zin;
       }
   } else {
-    for (int k = k0; k < k1; ++k) {
-      zin = -lo[k] * zin + b[k];
-      y[k] = zin;
+    for (int j = 0; j < cnt; ++j) {
+      zin = -lo[at(j)] * zin + b[at(j)];
+      y[at(j)] = zin;
     }
   }
   __syncthreads();  // the LDS slots are reused by the second scan
@@ -432,8 +474,8 @@ __device__ __forceinline__ void tridiag_solve_wg(const double* __restrict__ lo, 
     // rl <- -c/u (the coupling), rz <- z/u (the offset)
 #pragma unroll
     for (int j = 0; j < kTriReg; ++j) {
-      const double ui = j < cnt ? uinv[k0 + j] : 0.0;
-      rl[j] = j < cnt ? -c[k0 + j] * ui : 0.0;
+      const double ui = j < cnt ? uinv[at(j)] : 0.0;
+      rl[j] = j < cnt ? -c[at(j)] * ui : 0.0;
       rz[j] *= ui;
     }
 #pragma unroll
@@ -452,19 +494,19 @@ __device__ __forceinline__ void tridiag_solve_wg(const double* __restrict__ lo, 
       }
 #pragma unroll
     for (int j = 0; j < kTriReg; ++j)
-      if (j < cnt) y[k0 + j] = rz[j];
+      if (j < cnt) y[at(j)] = rz[j];
   } else {
-    for (int k = k1 - 1; k >= k0; --k) {
-      const double ui = uinv[k];
-      A = -c[k] * ui * A;
-      B = -c[k] * ui * B + y[k] * ui;
+    for (int j = cnt - 1; j >= 0; --j) {
+      const double ui = uinv[at(j)];
+      A = -c[at(j)] * ui * A;
+      B = -c[at(j)] * ui * B + y[at(j)] * ui;
     }
     scan_compose(A, B, true, wa, wb);
     double yin = B;
-    for (int k = k1 - 1; k >= k0; --k) {
-      const double ui = uinv[k];
-      yin = -c[k] * ui * yin + y[k] * ui;
-      y[k] = yin;
+    for (int j = cnt - 1; j >= 0; --j) {
+      const double ui = uinv[at(j)];
+      yin = -c[at(j)] * ui * yin + y[at(j)] * ui;
+      y[at(j)] = yin;
     }
   }
 }
@@ -475,7 +517,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag_solve(const double* __r
                                                                 const double* __restrict__ b, double* __restrict__ y,
                                                                 int n) {
   __shared__ double wa[kTriWaves], wb[kTriWaves];
-  tridiag_solve_wg(lo, uinv, c, b, y, n, wa, wb);
+  tridiag_solve_wg<false>(lo, uinv, c, b, y, n, wa, wb);
 }
 
 void tridiag_factor(const double* a, const double* d, const double* c, int n, double* lo, double* uinv, int* info,
@@ -738,7 +780,11 @@ void cons_sub_Zy(const double* Z, const double* yb, int nb, int np, double* yp, 
 //      border rows' dot products wb = rows . x and of Z^T wp;
 //   2. k_proj_solve (one workgroup): the partial sums, yb, and Kpp^-1 wp;
 //   3. k_apply_CT_z: out = x - C^T y with yp corrected by -Z yb per row.
+// wp, yp and the factors of Kpp are chunk-transposed (tri_chunk_pos with
+// m = ceil(np / kTriThreads)) so that the one-workgroup solve loads them
+// coalesced; Z and everything else are in row order.
 constexpr int kProjBlocks = 64, kProjSlots = 2 * kProjMaxBorder;
+static_assert(kProjBlocks == 64 && kProjSlots == kTriWaves, "k_proj_solve reduces one slot per wave");
 
 __global__ __launch_bounds__(256) void k_proj_rows(const double* __restrict__ geo, const int2* __restrict__ edges,
                                                    const int* __restrict__ path_edge, int np,
@@ -749,6 +795,7 @@ __global__ __launch_bounds__(256) void k_proj_rows(const double* __restrict__ ge
 #pragma unroll
   for (int q = 0; q < kProjSlots; ++q) acc[q] = 0.0;
   const int nmax = max(np, nV);
+  const int m = (np + kTriThreads - 1) / kTriThreads;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < nmax; i += gridDim.x * 256) {
     if (i < np) {
       const int I = path_edge[i];
@@ -756,7 +803,7 @@ __global__ __launch_bounds__(256) void k_proj_rows(const double* __restrict__ ge
       const double* g = geo + 8 * (size_t)I;
       const double w = g[1] * (x[3 * e.x] - x[3 * e.y]) + g[2] * (x[3 * e.x + 1] - x[3 * e.y + 1]) +
                        g[3] * (x[3 * e.x + 2] - x[3 * e.y + 2]);
-      wp[i] = w;
+      wp[tri_chunk_pos(i, m)] = w;
 #pragma unroll
       for (int r = 0; r < kProjMaxBorder; ++r)
         if (r < nb) acc[kProjMaxBorder + r] += Z[(size_t)r * np + i] * w;
@@ -774,6 +821,7 @@ __global__ __launch_bounds__(256) void k_proj_rows(const double* __restrict__ ge
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
 #pragma unroll
   for (int q = 0; q < kProjSlots; ++q) {
+    if ((q % kProjMaxBorder) >= nb) continue;  // unused slot (uniform)
     double v = acc[q];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     if (lane == 0) sred[w][q] = v;
@@ -781,7 +829,8 @@ __global__ __launch_bounds__(256) void k_proj_rows(const double* __restrict__ ge
   __syncthreads();
   if (threadIdx.x < kProjSlots) {
     const int q = threadIdx.x;
-    part[(size_t)blockIdx.x * kProjSlots + q] = ((sred[0][q] + sred[1][q]) + sred[2][q]) + sred[3][q];
+    part[(size_t)blockIdx.x * kProjSlots + q] =
+        (q % kProjMaxBorder) < nb ? ((sred[0][q] + sred[1][q]) + sred[2][q]) + sred[3][q] : 0.0;
   }
 }
 
@@ -793,16 +842,13 @@ __global__ __launch_bounds__(kTriThreads) void k_proj_solve(const double* __rest
                                                            const double* __restrict__ wp, double* __restrict__ yp,
                                                            double* __restrict__ yb, int np) {
   __shared__ double wa[kTriWaves], wbs[kTriWaves];
-  __shared__ double sp[kProjBlocks][kProjSlots + 1];
   __shared__ double tot[kProjSlots];
-  const int t = threadIdx.x;
-  const int q = t % kProjSlots, blk = t / kProjSlots;  // 1024 threads = 64 blocks x 16 slots
-  sp[blk][q] = blk < nblk ? part[(size_t)blk * kProjSlots + q] : 0.0;
-  __syncthreads();
-  if (t < kProjSlots) {
-    double v = 0.0;
-    for (int k = 0; k < kProjBlocks; ++k) v += sp[k][t];
-    tot[t] = v;
+  const int t = threadIdx.x, lane = t % 64;
+  {  // wave q sums slot q over the workgroups of k_proj_rows
+    const int q = t / 64;
+    double v = (lane < nblk && (q % kProjMaxBorder) < nb) ? part[(size_t)lane * kProjSlots + q] : 0.0;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) tot[q] = v;
   }
   __syncthreads();
   if (t < nb) {  // yb = S^-1 (wb - Z^T wp)
@@ -810,7 +856,7 @@ __global__ __launch_bounds__(kTriThreads) void k_proj_solve(const double* __rest
     for (int j = 0; j < nb; ++j) v += Sinv[t * nb + j] * (tot[j] - tot[kProjMaxBorder + j]);
     yb[t] = v;
   }
-  if (np > 0) tridiag_solve_wg(lo, uinv, tc, wp, yp, np, wa, wbs);
+  if (np > 0) tridiag_solve_wg<true>(lo, uinv, tc, wp, yp, np, wa, wbs);
 }
 
 // out_v = in_v - [ sum_{path rows k at v} s(v) T_I (yp_k - (Z yb)_k) + sum_r yb[r] rows[r][v] ]
@@ -823,6 +869,7 @@ __global__ __launch_bounds__(256) void k_apply_CT_z(const double* __restrict__ g
                                                     const double* __restrict__ in, double* __restrict__ out) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nV) return;
+  const int m = (np + kTriThreads - 1) / kTriThreads;
   double ybr[kProjMaxBorder];
 #pragma unroll
   for (int r = 0; r < kProjMaxBorder; ++r) ybr[r] = r < nb ? yb[r] : 0.0;
@@ -831,7 +878,7 @@ __global__ __launch_bounds__(256) void k_apply_CT_z(const double* __restrict__ g
     const int I = inc[k] >> 1;
     const int pr = edge_path_row[I];
     if (pr < 0) continue;
-    double y = yp[pr];
+    double y = yp[tri_chunk_pos(pr, m)];
 #pragma unroll
     for (int r = 0; r < kProjMaxBorder; ++r)
       if (r < nb) y -= Z[(size_t)r * np + pr] * ybr[r];
@@ -847,17 +894,38 @@ __global__ __launch_bounds__(256) void k_apply_CT_z(const double* __restrict__ g
 }
 
 void cons_project_fused(const double* geo, const int2* edges, const int* path_edge, int np, const double* rows,
-                        int nb, const double* Z, const double* Sinv, const double* lo, const double* uinv,
-                        const double* tc, const int* inc_off, const int* inc, const int* edge_path_row, int nV,
-                        const double* in, double* out, double* part, double* wp, double* yp, double* yb,
+                        int nb, const double* Z, const double* Sinv, const double* lo_ch, const double* uinv_ch,
+                        const double* tc_ch, const int* inc_off, const int* inc, const int* edge_path_row, int nV,
+                        const double* in, double* out, double* part, double* wp_ch, double* yp_ch, double* yb,
                         hipStream_t s) {
   const int nblk = std::min(kProjBlocks, std::max(1, cdiv(std::max(np, nV), 256)));
-  hipLaunchKernelGGL(k_proj_rows, dim3(nblk), dim3(256), 0, s, geo, edges, path_edge, np, rows, nb, Z, nV, in, wp,
-                     part);
-  hipLaunchKernelGGL(k_proj_solve, dim3(1), dim3(kTriThreads), 0, s, (const double*)part, nblk, nb, Sinv, lo, uinv,
-                     tc, (const double*)wp, yp, yb, np);
+  hipLaunchKernelGGL(k_proj_rows, dim3(nblk), dim3(256), 0, s, geo, edges, path_edge, np, rows, nb, Z, nV, in,
+                     wp_ch, part);
+  hipLaunchKernelGGL(k_proj_solve, dim3(1), dim3(kTriThreads), 0, s, (const double*)part, nblk, nb, Sinv, lo_ch,
+                     uinv_ch, tc_ch, (const double*)wp_ch, yp_ch, yb, np);
   hipLaunchKernelGGL(k_apply_CT_z, dim3(cdiv(nV, 256)), dim3(256), 0, s, geo, inc_off, inc, edge_path_row,
-                     (const double*)yp, Z, np, rows, (const double*)yb, nb, nV, in, out);
+                     (const double*)yp_ch, Z, np, rows, (const double*)yb, nb, nV, in, out);
+}
+
+// Copies of the factors l, 1/u and the coupling c of an n-row tridiagonal
+// system in the chunk-transposed order of the one-workgroup solve.
+__global__ void k_tri_chunk(const double* __restrict__ lo, const double* __restrict__ uinv,
+                            const double* __restrict__ c, int n, double* __restrict__ lo_ch,
+                            double* __restrict__ uinv_ch, double* __restrict__ c_ch) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int p = tri_chunk_pos(k, (n + kTriThreads - 1) / kTriThreads);
+  lo_ch[p] = lo[k];
+  uinv_ch[p] = uinv[k];
+  c_ch[p] = c[k];
+}
+
+int tri_chunk_size(int n) { return n <= 0 ? 1 : cdiv(n, kTriThreads) * kTriThreads; }
+
+void tridiag_chunk_copy(const double* lo, const double* uinv, const double* c, int n, double* lo_ch,
+                        double* uinv_ch, double* c_ch, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_tri_chunk, dim3(cdiv(n, 256)), dim3(256), 0, s, lo, uinv, c, n, lo_ch, uinv_ch, c_ch);
 }
 
 // ---------------------------------------------------------------------------

@@ -28,6 +28,9 @@ struct Cons {
   double *wp = nullptr, *yp = nullptr, *wb = nullptr, *yb = nullptr, *dots = nullptr, *rhs = nullptr;
   double* small = nullptr;
   double* part = nullptr;  // partial sums of the three-launch projector
+  // the three-launch projector's copies of the path factors and its work
+  // vectors, in the one-workgroup solve's chunk-transposed order
+  double *tri_ch = nullptr, *wp_ch = nullptr, *yp_ch = nullptr;
 };
 
 // Dense FP64 saddle solve on one curve: H = Abar + C^T C (Cholesky),

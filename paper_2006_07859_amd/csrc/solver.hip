@@ -192,7 +192,7 @@ void cons_free(Cons& k) {
   for (int* p : ip)
     if (p) hipFree(p);
   double* dp[] = {k.x0, k.len0, k.ones, k.geo, k.geo_eval, k.vals, k.rows, k.ta, k.td, k.tc, k.Kpb, k.Z, k.Sinv,
-                  k.tri_scratch, k.wp, k.yp, k.wb, k.yb, k.dots, k.rhs, k.small, k.part};
+                  k.tri_scratch, k.wp, k.yp, k.wb, k.yb, k.dots, k.rhs, k.small, k.part, k.tri_ch, k.wp_ch, k.yp_ch};
   for (double* p : dp)
     if (p) hipFree(p);
   k = Cons();
@@ -262,6 +262,9 @@ rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask) {
   RC_TRY(dalloc(&k.dots, (size_t)std::max(k.nb * k.nb, 4)));
   RC_TRY(dalloc(&k.small, (size_t)std::max(k.nb * k.nb, 8)));
   RC_TRY(dalloc(&k.part, (size_t)64 * 2 * kProjMaxBorder));
+  RC_TRY(dalloc(&k.tri_ch, 3 * (size_t)tri_chunk_size(k.np)));
+  RC_TRY(dalloc(&k.wp_ch, tri_chunk_size(k.np)));
+  RC_TRY(dalloc(&k.yp_ch, tri_chunk_size(k.np)));
   std::vector<double> ones(nE, 1.0);
   RC_HIP(hipMemcpy(k.ones, ones.data(), sizeof(double) * nE, hipMemcpyHostToDevice));
   RC_HIP(hipMemset(k.x0, 0, sizeof(double) * 3));
@@ -313,6 +316,8 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma)
       set_error("edge-length constraint Gram matrix is not positive definite");
       return RC_ERR_SINGULAR;
     }
+    const size_t nc = tri_chunk_size(np);
+    tridiag_chunk_copy(lo, uinv, k.tc, np, k.tri_ch, k.tri_ch + nc, k.tri_ch + 2 * nc, s);
   }
   if (nb > 0) {
     for (int r = 0; r < nb; ++r)
@@ -357,9 +362,10 @@ void cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double*
     return;
   }
   if (k.nb <= kProjMaxBorder) {
-    cons_project_fused(k.geo, cv.edges, k.path_edge, k.np, k.rows, k.nb, k.Z, k.Sinv, k.tri_scratch,
-                       k.tri_scratch + k.np, k.tc, cv.inc_off, cv.inc, k.edge_path_row, nV, in, out, k.part, k.wp,
-                       k.yp, k.yb, s);
+    const size_t nc = tri_chunk_size(k.np);
+    cons_project_fused(k.geo, cv.edges, k.path_edge, k.np, k.rows, k.nb, k.Z, k.Sinv, k.tri_ch, k.tri_ch + nc,
+                       k.tri_ch + 2 * nc, cv.inc_off, cv.inc, k.edge_path_row, nV, in, out, k.part, k.wp_ch,
+                       k.yp_ch, k.yb, s);
     return;
   }
   cons_path_apply(k.geo, cv.edges, k.path_edge, k.np, in, nV, 1, k.wp, s);
