@@ -13,12 +13,32 @@ int dot_scratch_size(int m);
 void vec_trial(const double* gamma, const double* g, const double* gg, double tau, double* out, int n,
                hipStream_t s);
 
-// Tridiagonal systems: factorisation (l, 1/u; info[0] = 0 on success) and
-// solves by parallel scans in one workgroup.
-void tridiag_factor(const double* a, const double* d, const double* c, int n, double* lo, double* uinv, int* info,
-                    hipStream_t s);
-void tridiag_solve(const double* lo, const double* uinv, const double* c, const double* b, double* y, int n,
-                   hipStream_t s);
+// Tridiagonal systems, block-partitioned (see k_linalg.hip): kSpThreads
+// threads per block of S = kSpThreads m rows, at most kSpMaxB blocks.
+constexpr int kTriThreads = 1024, kTriWaves = kTriThreads / 64;
+constexpr int kSpThreads = 256, kSpWaves = kSpThreads / 64, kSpMaxM = 8, kSpMaxB = 512;
+struct TriBlocks {
+  int n = 0;   // rows
+  int S = 1;   // rows per block
+  int B = 1;   // blocks (a single block when n <= kTriThreads)
+  int m = 1;   // rows per thread
+  int nr = 0;  // size of the reduced boundary system, 2 (B - 1)
+};
+TriBlocks tri_blocks(int n);
+struct TriSys {
+  TriBlocks L;
+  const double *lo = nullptr, *uinv = nullptr, *c = nullptr;  // block-local factors l, 1/u and the couplings c
+  const double *V = nullptr, *W = nullptr;                    // spikes [n] each
+  const double* Rt = nullptr;                                 // inverse of the reduced system, transposed [nr][nr]
+};
+// Block-local factorisation, spikes (VW: [2 n], V then W) and the reduced
+// inverse Rt; a, d, c: the rows' coefficients; lo, uinv: [n]; scratch: [2 n];
+// info: device int, 0 on success, else 1 + a row with a non-positive pivot.
+void tri_prepare(const double* a, const double* d, const double* c, const TriBlocks& L, double* lo, double* uinv,
+                 double* VW, double* Rt, double* scratch, int* info, hipStream_t s);
+// y_r = K^-1 rhs_r for m columns (ldr, ldy apart); g: [m n] and U: [m nr] scratch.
+void tri_solve(const TriSys& T, const double* rhs, int ldr, double* y, int ldy, int m, double* g, double* U,
+               hipStream_t s);
 void dense_gemv(const double* A, const double* x, double* y, int n, hipStream_t s);
 
 // constraint pieces
@@ -40,19 +60,40 @@ void cons_border_solve(const double* Sinv, const double* wb, const double* dots,
 void cons_sub_Zy(const double* Z, const double* yb, int nb, int np, double* yp, hipStream_t s);
 // P x in three launches when nb <= kProjMaxBorder (in and out may alias:
 // every output entry is written by the last launch from its own input
-// entry).  part: device double [64 * 2 * kProjMaxBorder]; yb: [nb].  The
-// factors lo_ch, uinv_ch, tc_ch (from tridiag_chunk_copy) and the work vectors
-// wp_ch, yp_ch are in the solve's chunk-transposed order, tri_chunk_size(np)
-// entries each.
+// entry); with packed rows and vertices (vertex degree <= 2), levels with
+// np, nV <= 1024 take one launch.
 constexpr int kProjMaxBorder = 8;
-void cons_project_fused(const double* geo, const int2* edges, const int* path_edge, int np, const double* rows,
-                        int nb, const double* Z, const double* Sinv, const double* lo_ch, const double* uinv_ch,
-                        const double* tc_ch, const int* inc_off, const int* inc, const int* edge_path_row, int nV,
-                        const double* in, double* out, double* part, double* wp_ch, double* yp_ch, double* yb,
-                        hipStream_t s);
-int tri_chunk_size(int n);
-void tridiag_chunk_copy(const double* lo, const double* uinv, const double* c, int n, double* lo_ch,
-                        double* uinv_ch, double* c_ch, hipStream_t s);
+struct __align__(16) ProjRow {  // path row: T_I and the ends of edge I
+  double t[3];
+  int2 ends;
+};
+struct __align__(16) ProjVert {  // up to two incident path rows and s(v) T_I for each (-1: none)
+  double c[2][3];
+  int row[2];
+};
+struct ProjData {
+  int np = 0, nb = 0, nV = 0;
+  const double* geo = nullptr;
+  const int2* edges = nullptr;
+  const int* path_edge = nullptr;
+  const double* rows = nullptr;  // border rows [nb][nV][3]
+  const double* Z = nullptr;     // [nb][np]
+  const double* Sinv = nullptr;  // [nb][nb]
+  TriBlocks tri;                 // the path block's partition
+  const double *lo = nullptr, *uinv = nullptr, *tc = nullptr;  // block-local factors and couplings
+  const double *V = nullptr, *W = nullptr, *Rt = nullptr;     // spikes and reduced inverse (tri_prepare)
+  const int *inc_off = nullptr, *inc = nullptr, *edge_path_row = nullptr;
+  const ProjRow* prow = nullptr;    // packed rows [np] (null: from path_edge, edges, geo)
+  const ProjVert* pvert = nullptr;  // packed vertices [nV] (null: from the incidence lists)
+  double* part = nullptr;           // [max(B, 64) * 2 * kProjMaxBorder]
+  double* g = nullptr;              // block-local solution [np]
+  double* U = nullptr;              // boundary values [nr]
+  double* yb = nullptr;             // [nb]
+};
+void cons_project_fused(const ProjData& d, const double* in, double* out, hipStream_t s);
+void cons_project_pack(const double* geo, const int2* edges, const int* path_edge, int np, const int* inc_off,
+                       const int* inc, const int* edge_path_row, int nV, ProjRow* prow, ProjVert* pvert,
+                       hipStream_t s);
 
 // dense direct path
 void dense_build_H(const double* A, const double* CtC, int nV, double* H, hipStream_t s);

@@ -291,18 +291,29 @@ void dense_gemv(const double* A, const double* x, double* y, int n, hipStream_t 
 }
 
 // ---------------------------------------------------------------------------
-// tridiagonal systems: Thomas factorisation once, solves by parallel scans
+// tridiagonal systems: block-partitioned factorisation and solves
 // ---------------------------------------------------------------------------
 // Rows k < n: a[k] y[k-1] + d[k] y[k] + c[k] y[k+1] = b[k] with a[0] = c[n-1] = 0
-// (zero couplings also separate independent segments).  The factorisation
-// l[k] = a[k] / u[k-1], u[k] = d[k] - l[k] c[k-1] is a nonlinear recurrence and
-// runs in one wave once per system; it stores l and 1/u.  A solve is two
-// first-order linear recurrences, forward  z[k] = b[k] - l[k] z[k-1]  and
-// backward  y[k] = (z[k] - c[k] y[k+1]) / u[k].  Each is an affine map per row;
-// one workgroup composes the maps of contiguous chunks per thread (held in
-// registers up to 16 rows per thread), scans the chunk composites across the
-// workgroup (wave shuffles, then one LDS exchange of the 16 wave totals), and
-// then replays its chunk.
+// (zero couplings also separate independent segments).  The rows are cut into
+// B blocks of S consecutive rows; with D the block-diagonal part and R the
+// couplings across block boundaries (c at a block's last row, a at the next
+// block's first row), K y = b becomes (I + D^-1 R) y = g with g = D^-1 b.
+// D^-1 R is zero except for two columns per boundary, the spikes
+//   V_q = D_q^-1 (c[e_q] e_last),   W_q = D_q^-1 (a[f_q] e_first)
+// (e_q, f_q: last and first row of block q), so on block q
+//   y = g - V_q y[f_{q+1}] - W_q y[e_{q-1}],
+// and the 2 (B - 1) boundary values (y[e_q], y[f_{q+1}]) solve a reduced
+// system that is block tridiagonal in 2 x 2 blocks.  Its inverse is formed
+// once per factorisation (block elimination, one column per thread); a solve
+// is then a local solve per block (B workgroups in parallel), one small dense
+// product and the spike correction.
+// Block-local factorisation (one wave per block): l[k] = a[k] / u[k-1],
+// u[k] = d[k] - l[k] c[k-1], restarted (l = 0) at each block's first row, and
+// stored as l and 1/u.  A local solve is two first-order linear recurrences,
+// forward z[k] = b[k] - l[k] z[k-1] and backward y[k] = (z[k] - c[k] y[k+1]) / u[k],
+// each an affine map per row: a workgroup composes the maps of each thread's
+// rows, scans the composites (wave shuffles, then the wave totals) and
+// replays its rows.
 // The system is symmetric positive definite (a constraint Gram matrix), so
 // the factorisation needs no pivoting.
 __device__ __forceinline__ double readlane_f64(double v, int j) {
@@ -312,49 +323,67 @@ __device__ __forceinline__ double readlane_f64(double v, int j) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// One wave: the coefficients of 64 rows at a time are loaded coalesced and
-// handed to the recurrence by lane reads; lane j keeps row j's factors.
+TriBlocks tri_blocks(int n) {
+  TriBlocks L;
+  L.n = n;
+  if (n <= kTriThreads) {  // one block (the one-workgroup projector relies on it)
+    L.B = 1;
+    L.S = std::max(n, 1);
+    L.m = std::max(1, cdiv(L.S, kSpThreads));
+  } else {
+    L.m = std::min(kSpMaxM, cdiv(n, kSpThreads * 64));
+    L.S = kSpThreads * L.m;
+    L.B = cdiv(n, L.S);
+  }
+  L.nr = 2 * (L.B - 1);
+  return L;
+}
+
+// One wave per block: the coefficients of 64 rows at a time are loaded
+// coalesced and handed to the recurrence by lane reads; lane j keeps row j's
+// factors.  The recurrence is carried in 1/u: l = a (1/u_prev),
+// u = d - l c_prev, and 1/u by the hardware reciprocal and two Newton-Raphson
+// steps y <- y + y (1 - u y), each of which squares the estimate's relative
+// error (full FP64 precision for the u in [1, 2] of the edge-length Gram
+// matrix: diagonal 2, couplings of size <= 1).
 __global__ __launch_bounds__(64) void k_tridiag_factor(const double* __restrict__ a, const double* __restrict__ d,
-                                                       const double* __restrict__ c, int n, double* __restrict__ lo,
-                                                       double* __restrict__ uinv, int* __restrict__ info) {
-  if (blockIdx.x != 0) return;
+                                                       const double* __restrict__ c, int n, int S,
+                                                       double* __restrict__ lo, double* __restrict__ uinv,
+                                                       int* __restrict__ info) {
   const int lane = threadIdx.x;
-  double u_prev = 1.0, c_prev = 0.0;
+  const int r0 = blockIdx.x * S, r1 = min(n, r0 + S);
+  double ui_prev = 0.0, c_prev = 0.0;  // the block's first row has l = 0
   int bad = 0;
-  for (int k0 = 0; k0 < n; k0 += 64) {
+  for (int k0 = r0; k0 < r1; k0 += 64) {
     const int k = k0 + lane;
-    const double ak = k < n ? a[k] : 0.0, dk = k < n ? d[k] : 1.0, ck = k < n ? c[k] : 0.0;
-    const int cnt = min(64, n - k0);
+    const double ak = k < r1 ? a[k] : 0.0, dk = k < r1 ? d[k] : 1.0, ck = k < r1 ? c[k] : 0.0;
+    const int cnt = min(64, r1 - k0);
     double my_l = 0.0, my_ui = 0.0;
     for (int j = 0; j < cnt; ++j) {
-      const double aj = readlane_f64(ak, j), dj = readlane_f64(dk, j);
-      const double l = (k0 + j == 0) ? 0.0 : aj / u_prev;
-      const double u = dj - l * c_prev;
+      const double l = readlane_f64(ak, j) * ui_prev;
+      const double u = fma(-l, c_prev, readlane_f64(dk, j));
       if (!(u > 0.0)) bad = k0 + j + 1;
-      if (lane == j) {
-        my_l = l;
-        my_ui = 1.0 / u;
-      }
-      u_prev = u;
+      double y = __builtin_amdgcn_rcp(u);
+      y = fma(y, fma(-u, y, 1.0), y);
+      y = fma(y, fma(-u, y, 1.0), y);
+      my_l = lane == j ? l : my_l;
+      my_ui = lane == j ? y : my_ui;
+      ui_prev = y;
       c_prev = readlane_f64(ck, j);
     }
-    if (k < n) {
+    if (k < r1) {
       lo[k] = my_l;
       uinv[k] = my_ui;
     }
   }
-  if (lane == 0) info[0] = bad;
+  if (lane == 0 && bad) atomicMax(info, bad);
 }
 
-constexpr int kTriThreads = 1024;
-constexpr int kTriWaves = kTriThreads / 64;
-constexpr int kTriReg = 16;  // rows per thread held in registers (n <= 16,384); longer chunks reload
-
 // Composite affine maps: (a, b) is v -> a v + b.  scan_compose returns, for
-// every thread, the composite of all maps of the threads before it (in scan
-// order: increasing t, or decreasing t when `rev`), i.e. the map from the
-// value entering the recurrence to the value entering this thread's chunk.
-// Within a wave: shuffles; across waves: one LDS exchange (2 barriers).
+// every thread of an NW-wave workgroup, the composite of the maps of all
+// threads before it in scan order (increasing thread index, or decreasing
+// when rev), the first thread getting the identity (1, 0).  wa, wb: LDS [NW].
+template <int NW>
 __device__ __forceinline__ void scan_compose(double& a, double& b, bool rev, double* wa, double* wb) {
   const int t = threadIdx.x, lane = t % 64, w = t / 64;
   // inclusive scan inside the wave, in scan order (lane order reversed for rev)
@@ -384,10 +413,10 @@ __device__ __forceinline__ void scan_compose(double& a, double& b, bool rev, dou
   }
   __syncthreads();
   if (w == 0) {  // exclusive scan of the wave totals in scan order, in place: lane q holds the q-th total
-    const int ww = rev ? kTriWaves - 1 - lane : lane;
-    double ta = lane < kTriWaves ? wa[ww] : 1.0, tb = lane < kTriWaves ? wb[ww] : 0.0;
+    const int ww = rev ? NW - 1 - lane : lane;
+    double ta = lane < NW ? wa[ww] : 1.0, tb = lane < NW ? wb[ww] : 0.0;
 #pragma unroll
-    for (int off = 1; off < kTriWaves; off <<= 1) {
+    for (int off = 1; off < NW; off <<= 1) {
       const double pa = __shfl_up(ta, off, 64), pb = __shfl_up(tb, off, 64);
       if (lane >= off) {
         tb = ta * pb + tb;
@@ -399,7 +428,7 @@ __device__ __forceinline__ void scan_compose(double& a, double& b, bool rev, dou
       xa = 1.0;
       xb = 0.0;
     }
-    if (lane < kTriWaves) {
+    if (lane < NW) {
       wa[ww] = xa;
       wb[ww] = xb;
     }
@@ -411,125 +440,206 @@ __device__ __forceinline__ void scan_compose(double& a, double& b, bool rev, dou
   b = ea * pb + eb;
 }
 
-// y = K^-1 b for the factorised tridiagonal K, by one workgroup of
-// kTriThreads threads (every thread must call it); wa, wb: LDS [kTriWaves].
-// Thread t owns rows t m .. t m + m - 1 (m = ceil(n / kTriThreads)).  With
-// Chunked, every array is stored chunk-transposed: row t m + j at position
-// j kTriThreads + t (tri_chunk_pos), so that the j-th row of all threads is one
-// coalesced load; otherwise arrays are in row order.
-__host__ __device__ __forceinline__ int tri_chunk_pos(int k, int m) { return (k % m) * kTriThreads + k / m; }
-
-template <bool Chunked>
-__device__ __forceinline__ void tridiag_solve_wg(const double* __restrict__ lo, const double* __restrict__ uinv,
-                                                 const double* __restrict__ c, const double* __restrict__ b,
-                                                 double* __restrict__ y, int n, double* wa, double* wb) {
+// Local solve on block blk by a workgroup of kSpThreads threads (all must
+// call it): thread t holds the right-hand sides of rows blk S + t m + j
+// (j < m) in v and gets the block-local solution back.
+__device__ __forceinline__ void tri_local_solve(const double* __restrict__ lo, const double* __restrict__ uinv,
+                                                const double* __restrict__ c, const TriBlocks& L, int blk,
+                                                double (&v)[kSpMaxM], double* wa, double* wb) {
   const int t = threadIdx.x;
-  const int m = (n + kTriThreads - 1) / kTriThreads;
-  const int k0 = min(n, t * m), k1 = min(n, k0 + m), cnt = k1 - k0;
-  // position of the thread's j-th row
-  auto at = [&](int j) { return Chunked ? j * kTriThreads + t : k0 + j; };
-  const bool reg = m <= kTriReg;
-  double rl[kTriReg], rz[kTriReg];
-  // forward: z[k] = -l[k] z[k-1] + b[k]; chunk composite z_out = A z_in + B
+  const int r1 = min(L.n, (blk + 1) * L.S);
+  const int k0 = blk * L.S + t * L.m;
+  const int cnt = max(0, min(L.m, r1 - k0));
+  double rl[kSpMaxM], rq[kSpMaxM];
   double A = 1.0, B = 0.0;
-  if (reg) {
 #pragma unroll
-    for (int j = 0; j < kTriReg; ++j) {
-      rl[j] = j < cnt ? lo[at(j)] : 0.0;
-      rz[j] = j < cnt ? b[at(j)] : 0.0;
+  for (int j = 0; j < kSpMaxM; ++j)
+    if (j < cnt) {
+      rl[j] = lo[k0 + j];
+      A = -rl[j] * A;
+      B = -rl[j] * B + v[j];
     }
+  scan_compose<kSpWaves>(A, B, false, wa, wb);
+  double zin = B;  // z before the thread's rows (z = 0 before the block)
 #pragma unroll
-    for (int j = 0; j < kTriReg; ++j)
-      if (j < cnt) {
-        A = -rl[j] * A;
-        B = -rl[j] * B + rz[j];
-      }
-  } else {
-    for (int j = 0; j < cnt; ++j) {
-      const double l = lo[at(j)];
-      A = -l * A;
-      B = -l * B + b[at(j)];
+  for (int j = 0; j < kSpMaxM; ++j)
+    if (j < cnt) {
+      zin = -rl[j] * zin + v[j];
+      v[j] = zin;
     }
-  }
-  scan_compose(A, B, false, wa, wb);
-  double zin = B;  // z before the chunk (z[-1] = 0)
-  if (reg) {
-#pragma unroll
-    for (int j = 0; j < kTriReg; ++j)
-      if (j < cnt) {
-        zin = -rl[j] * zin + rz[j];
-        rz[j] = zin;
-      }
-  } else {
-    for (int j = 0; j < cnt; ++j) {
-      zin = -lo[at(j)] * zin + b[at(j)];
-      y[at(j)] = zin;
-    }
-  }
   __syncthreads();  // the LDS slots are reused by the second scan
-  // backward: y[k] = -c[k] uinv[k] y[k+1] + z[k] uinv[k], scanned from the end
+#pragma unroll
+  for (int j = 0; j < kSpMaxM; ++j)
+    if (j < cnt) {
+      const double ui = uinv[k0 + j];
+      rq[j] = -c[k0 + j] * ui;  // coupling
+      v[j] *= ui;               // offset
+    }
   A = 1.0;
   B = 0.0;
-  if (reg) {
-    // rl <- -c/u (the coupling), rz <- z/u (the offset)
 #pragma unroll
-    for (int j = 0; j < kTriReg; ++j) {
-      const double ui = j < cnt ? uinv[at(j)] : 0.0;
-      rl[j] = j < cnt ? -c[at(j)] * ui : 0.0;
-      rz[j] *= ui;
+  for (int j = kSpMaxM - 1; j >= 0; --j)
+    if (j < cnt) {
+      A = rq[j] * A;
+      B = rq[j] * B + v[j];
     }
+  scan_compose<kSpWaves>(A, B, true, wa, wb);
+  double yin = B;  // y after the thread's rows (y = 0 after the block)
 #pragma unroll
-    for (int j = kTriReg - 1; j >= 0; --j)
-      if (j < cnt) {
-        A = rl[j] * A;
-        B = rl[j] * B + rz[j];
-      }
-    scan_compose(A, B, true, wa, wb);
-    double yin = B;  // y after the chunk (y[n] = 0)
-#pragma unroll
-    for (int j = kTriReg - 1; j >= 0; --j)
-      if (j < cnt) {
-        yin = rl[j] * yin + rz[j];
-        rz[j] = yin;
-      }
-#pragma unroll
-    for (int j = 0; j < kTriReg; ++j)
-      if (j < cnt) y[at(j)] = rz[j];
-  } else {
-    for (int j = cnt - 1; j >= 0; --j) {
-      const double ui = uinv[at(j)];
-      A = -c[at(j)] * ui * A;
-      B = -c[at(j)] * ui * B + y[at(j)] * ui;
+  for (int j = kSpMaxM - 1; j >= 0; --j)
+    if (j < cnt) {
+      yin = rq[j] * yin + v[j];
+      v[j] = yin;
     }
-    scan_compose(A, B, true, wa, wb);
-    double yin = B;
-    for (int j = cnt - 1; j >= 0; --j) {
-      const double ui = uinv[at(j)];
-      yin = -c[at(j)] * ui * yin + y[at(j)] * ui;
-      y[at(j)] = yin;
+}
+
+// g_r = D^-1 b_r for m right-hand sides (grid: blocks x m; columns ld apart)
+__global__ __launch_bounds__(kSpThreads) void k_tri_local(const double* __restrict__ lo,
+                                                          const double* __restrict__ uinv,
+                                                          const double* __restrict__ c, const TriBlocks L,
+                                                          const double* __restrict__ rhs, int ldr,
+                                                          double* __restrict__ g, int ldg) {
+  __shared__ double wa[kSpWaves], wb[kSpWaves];
+  const int blk = blockIdx.x, col = blockIdx.y;
+  const int k0 = blk * L.S + threadIdx.x * L.m;
+  const int cnt = max(0, min(L.m, min(L.n, (blk + 1) * L.S) - k0));
+  const double* b = rhs + (size_t)col * ldr;
+  double v[kSpMaxM];
+#pragma unroll
+  for (int j = 0; j < kSpMaxM; ++j) v[j] = j < cnt ? b[k0 + j] : 0.0;
+  tri_local_solve(lo, uinv, c, L, blk, v, wa, wb);
+  double* out = g + (size_t)col * ldg;
+#pragma unroll
+  for (int j = 0; j < kSpMaxM; ++j)
+    if (j < cnt) out[k0 + j] = v[j];
+}
+
+// Right-hand sides of the spikes: column 0 c[e_q] at each block's last row
+// (blocks before the last), column 1 a[f_q] at each block's first row (blocks
+// after the first).
+__global__ void k_spike_unit(const double* __restrict__ a, const double* __restrict__ c, const TriBlocks L,
+                             double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= L.n) return;
+  const int q = k / L.S, pos = k - q * L.S;
+  out[k] = (q < L.B - 1 && pos == L.S - 1) ? c[k] : 0.0;
+  out[L.n + k] = (q > 0 && pos == 0) ? a[k] : 0.0;
+}
+
+// The reduced system on the boundary values U_q = (y[e_q], y[f_{q+1}]),
+// q < B - 1 (rows of the spike equations at e_q and f_{q+1}):
+//   y[e_q] + V[e_q] y[f_{q+1}] + W[e_q] y[e_{q-1}] = g[e_q]
+//   y[f_{q+1}] + W[f_{q+1}] y[e_q] + V[f_{q+1}] y[f_{q+2}] = g[f_{q+1}].
+// Block elimination: D'_q = D_q - L_q D'_{q-1}^-1 R_{q-1} changes only the
+// (0, 1) entry of D_q = [[1, V[e_q]], [W[f_{q+1}], 1]] (L_q has W[e_q] at (0, 0),
+// R_{q-1} has V[f_q] at (1, 1)).  Thread 0 forms the 2 x 2 inverses; thread
+// j < nr then solves for column j of the inverse, using row j of Rt as its
+// scratch, and leaves Rt[j nr + i] = (M^-1)_ij.
+__global__ __launch_bounds__(kSpThreads) void k_spike_rinv(const double* __restrict__ V,
+                                                           const double* __restrict__ W, const TriBlocks L,
+                                                           double* __restrict__ Rt) {
+  __shared__ double dinv[kSpMaxB][4];
+  const int nq = L.B - 1, nr = L.nr, S = L.S;
+  if (threadIdx.x == 0) {
+    double prev01 = 0.0;  // (D'_{q-1}^-1)_01
+    for (int q = 0; q < nq; ++q) {
+      const int e = (q + 1) * S - 1, f = (q + 1) * S;
+      const double m00 = 1.0, m11 = 1.0, m10 = W[f];
+      const double m01 = V[e] - (q > 0 ? W[e] * V[(q) * S] * prev01 : 0.0);
+      const double det = m00 * m11 - m01 * m10;
+      dinv[q][0] = m11 / det;
+      dinv[q][1] = -m01 / det;
+      dinv[q][2] = -m10 / det;
+      dinv[q][3] = m00 / det;
+      prev01 = dinv[q][1];
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
+    double* x = Rt + (size_t)j * nr;
+    // forward: G'_q = G_q - L_q D'_{q-1}^-1 G'_{q-1} (only the first entry changes)
+    double p0 = 0.0, p1 = 0.0;  // G'_{q-1}
+    for (int q = 0; q < nq; ++q) {
+      double g0 = (2 * q == j) ? 1.0 : 0.0, g1 = (2 * q + 1 == j) ? 1.0 : 0.0;
+      if (q > 0) g0 -= W[(q + 1) * S - 1] * (dinv[q - 1][0] * p0 + dinv[q - 1][1] * p1);
+      x[2 * q] = g0;
+      x[2 * q + 1] = g1;
+      p0 = g0;
+      p1 = g1;
+    }
+    // backward: U_q = D'_q^-1 (G'_q - R_q U_{q+1})
+    double u1n = 0.0;  // U_{q+1}[1]
+    for (int q = nq - 1; q >= 0; --q) {
+      const double g0 = x[2 * q];
+      const double g1 = x[2 * q + 1] - (q < nq - 1 ? V[(q + 1) * S] * u1n : 0.0);
+      const double u0 = dinv[q][0] * g0 + dinv[q][1] * g1, u1 = dinv[q][2] * g0 + dinv[q][3] * g1;
+      x[2 * q] = u0;
+      x[2 * q + 1] = u1;
+      u1n = u1;
     }
   }
 }
 
-__global__ __launch_bounds__(kTriThreads) void k_tridiag_solve(const double* __restrict__ lo,
-                                                                const double* __restrict__ uinv,
-                                                                const double* __restrict__ c,
-                                                                const double* __restrict__ b, double* __restrict__ y,
-                                                                int n) {
-  __shared__ double wa[kTriWaves], wb[kTriWaves];
-  tridiag_solve_wg<false>(lo, uinv, c, b, y, n, wa, wb);
+// U_r = M^-1 (g_r[e_q], g_r[f_{q+1}])_q for m columns (grid: m)
+__global__ __launch_bounds__(kSpThreads) void k_tri_reduce(const double* __restrict__ g, int ldg, const TriBlocks L,
+                                                           const double* __restrict__ Rt, double* __restrict__ U) {
+  __shared__ double rhs[2 * (kSpMaxB - 1)];
+  const int col = blockIdx.y * gridDim.x + blockIdx.x, nr = L.nr;
+  const double* gc = g + (size_t)col * ldg;
+  for (int i = threadIdx.x; i < nr; i += blockDim.x) {
+    const int q = i / 2;
+    rhs[i] = gc[(i % 2 == 0) ? (q + 1) * L.S - 1 : (q + 1) * L.S];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nr; i += blockDim.x) {
+    double u = 0.0;
+    for (int j = 0; j < nr; ++j) u += Rt[(size_t)j * nr + i] * rhs[j];
+    U[(size_t)col * nr + i] = u;
+  }
 }
 
-void tridiag_factor(const double* a, const double* d, const double* c, int n, double* lo, double* uinv, int* info,
-                    hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_tridiag_factor, dim3(1), dim3(64), 0, s, a, d, c, n, lo, uinv, info);
+// y = g - V U[2q + 1] - W U[2 (q - 1)] on block q (grid: row blocks x m)
+__global__ void k_tri_correct(const double* __restrict__ g, int ldg, const double* __restrict__ V,
+                              const double* __restrict__ W, const double* __restrict__ U, const TriBlocks L,
+                              double* __restrict__ y, int ldy) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x, col = blockIdx.y;
+  if (k >= L.n) return;
+  const int q = k / L.S;
+  const double* Uc = U + (size_t)col * L.nr;
+  double v = g[(size_t)col * ldg + k];
+  if (q < L.B - 1) v -= V[k] * Uc[2 * q + 1];
+  if (q > 0) v -= W[k] * Uc[2 * (q - 1)];
+  y[(size_t)col * ldy + k] = v;
 }
 
-void tridiag_solve(const double* lo, const double* uinv, const double* c, const double* b, double* y, int n,
-                   hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_tridiag_solve, dim3(1), dim3(kTriThreads), 0, s, lo, uinv, c, b, y, n);
+void tri_prepare(const double* a, const double* d, const double* c, const TriBlocks& L, double* lo, double* uinv,
+                 double* VW, double* Rt, double* scratch, int* info, hipStream_t s) {
+  hipMemsetAsync(info, 0, sizeof(int), s);
+  if (L.n <= 0) return;
+  hipLaunchKernelGGL(k_tridiag_factor, dim3(L.B), dim3(64), 0, s, a, d, c, L.n, L.S, lo, uinv, info);
+  if (L.B == 1) {  // no boundaries: zero spikes
+    hipMemsetAsync(VW, 0, sizeof(double) * 2 * (size_t)L.n, s);
+    return;
+  }
+  hipLaunchKernelGGL(k_spike_unit, dim3(cdiv(L.n, 256)), dim3(256), 0, s, a, c, L, scratch);
+  hipLaunchKernelGGL(k_tri_local, dim3(L.B, 2), dim3(kSpThreads), 0, s, lo, uinv, c, L, (const double*)scratch,
+                     L.n, VW, L.n);
+  hipLaunchKernelGGL(k_spike_rinv, dim3(1), dim3(kSpThreads), 0, s, (const double*)VW, (const double*)(VW + L.n), L,
+                     Rt);
+}
+
+void tri_solve(const TriSys& T, const double* rhs, int ldr, double* y, int ldy, int m, double* g, double* U,
+               hipStream_t s) {
+  const TriBlocks& L = T.L;
+  if (L.n <= 0 || m <= 0) return;
+  if (L.B == 1) {
+    hipLaunchKernelGGL(k_tri_local, dim3(1, m), dim3(kSpThreads), 0, s, T.lo, T.uinv, T.c, L, rhs, ldr, y, ldy);
+    return;
+  }
+  hipLaunchKernelGGL(k_tri_local, dim3(L.B, m), dim3(kSpThreads), 0, s, T.lo, T.uinv, T.c, L, rhs, ldr, g, L.n);
+  hipLaunchKernelGGL(k_tri_reduce, dim3(m), dim3(kSpThreads), 0, s, (const double*)g, L.n, L, T.Rt, U);
+  hipLaunchKernelGGL(k_tri_correct, dim3(cdiv(L.n, 256), m), dim3(256), 0, s, (const double*)g, L.n, T.V, T.W,
+                     (const double*)U, L, y, ldy);
 }
 
 // ---------------------------------------------------------------------------
@@ -775,157 +885,361 @@ void cons_sub_Zy(const double* Z, const double* yb, int nb, int np, double* yp, 
 // block Kbb and their coupling Kpb, and Z = Kpp^-1 Kpb (columns), the Schur
 // complement solve of K y = (wp, wb) is
 //   yb = S^-1 (wb - Z^T wp),  yp = Kpp^-1 wp - Z yb,   S = Kbb - Kpb^T Z,
-// using Kpb^T Kpp^-1 = Z^T (Kpp is symmetric).
-//   1. k_proj_rows: wp = C_path x, and per-workgroup partial sums of the
-//      border rows' dot products wb = rows . x and of Z^T wp;
-//   2. k_proj_solve (one workgroup): the partial sums, yb, and Kpp^-1 wp;
-//   3. k_apply_CT_z: out = x - C^T y with yp corrected by -Z yb per row.
-// wp, yp and the factors of Kpp are chunk-transposed (tri_chunk_pos with
-// m = ceil(np / kTriThreads)) so that the one-workgroup solve loads them
-// coalesced; Z and everything else are in row order.
-constexpr int kProjBlocks = 64, kProjSlots = 2 * kProjMaxBorder;
-static_assert(kProjBlocks == 64 && kProjSlots == kTriWaves, "k_proj_solve reduces one slot per wave");
+// using Kpb^T Kpp^-1 = Z^T (Kpp is symmetric).  Kpp^-1 is the
+// block-partitioned solve above:
+//   1. k_proj_rows (one workgroup per block of path rows): wp = C_path x, the
+//      block-local solution g = D^-1 wp, and per-workgroup partial sums of
+//      the border rows' dot products wb = rows . x and of Z^T wp;
+//   2. k_proj_solve (one workgroup): the partial sums, yb, and the reduced
+//      boundary values U = M^-1 (g at the block boundaries);
+//   3. k_apply_CT_z: out = x - C^T y with yp = g - V U - W U - Z yb per row.
+// With vertex degree <= 2 (curves), the row data (T_I and the edge's ends)
+// and each vertex's incident path rows with their signed tangents s(v) T_I
+// are packed per level (ProjRow, ProjVert), so that a row or vertex needs one
+// load before the gathers.
+constexpr int kProjSlots = 2 * kProjMaxBorder;
 
-__global__ __launch_bounds__(256) void k_proj_rows(const double* __restrict__ geo, const int2* __restrict__ edges,
-                                                   const int* __restrict__ path_edge, int np,
-                                                   const double* __restrict__ rows, int nb,
-                                                   const double* __restrict__ Z, int nV, const double* __restrict__ x,
-                                                   double* __restrict__ wp, double* __restrict__ part) {
+// w = C_I x for path row i
+__device__ __forceinline__ double proj_row_value(const ProjData& d, int i, const double* __restrict__ x) {
+  double t0, t1, t2;
+  int a, b;
+  if (d.prow) {
+    const ProjRow p = d.prow[i];
+    t0 = p.t[0];
+    t1 = p.t[1];
+    t2 = p.t[2];
+    a = p.ends.x;
+    b = p.ends.y;
+  } else {
+    const int I = d.path_edge[i];
+    const int2 e = d.edges[I];
+    const double* g = d.geo + 8 * (size_t)I;
+    t0 = g[1];
+    t1 = g[2];
+    t2 = g[3];
+    a = e.x;
+    b = e.y;
+  }
+  return t0 * (x[3 * a] - x[3 * b]) + t1 * (x[3 * a + 1] - x[3 * b + 1]) + t2 * (x[3 * a + 2] - x[3 * b + 2]);
+}
+
+__global__ __launch_bounds__(kSpThreads) void k_proj_rows(const ProjData d, const double* __restrict__ x) {
+  __shared__ double wa[kSpWaves], wb[kSpWaves];
+  __shared__ double sred[kSpWaves][kProjSlots];
+  const int t = threadIdx.x, blk = blockIdx.x;
+  const int np = d.np, nV = d.nV, nb = d.nb;
+  const TriBlocks& L = d.tri;
   double acc[kProjSlots];
 #pragma unroll
   for (int q = 0; q < kProjSlots; ++q) acc[q] = 0.0;
-  const int nmax = max(np, nV);
-  const int m = (np + kTriThreads - 1) / kTriThreads;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < nmax; i += gridDim.x * 256) {
-    if (i < np) {
-      const int I = path_edge[i];
-      const int2 e = edges[I];
-      const double* g = geo + 8 * (size_t)I;
-      const double w = g[1] * (x[3 * e.x] - x[3 * e.y]) + g[2] * (x[3 * e.x + 1] - x[3 * e.y + 1]) +
-                       g[3] * (x[3 * e.x + 2] - x[3 * e.y + 2]);
-      wp[tri_chunk_pos(i, m)] = w;
+  // the thread's path rows
+  const int k0 = blk * L.S + t * L.m;
+  const int cnt = max(0, min(L.m, min(np, (blk + 1) * L.S) - k0));
+  double v[kSpMaxM];
+#pragma unroll
+  for (int j = 0; j < kSpMaxM; ++j) {
+    v[j] = 0.0;
+    if (j < cnt) {
+      const int i = k0 + j;
+      const double w = proj_row_value(d, i, x);
+      v[j] = w;
 #pragma unroll
       for (int r = 0; r < kProjMaxBorder; ++r)
-        if (r < nb) acc[kProjMaxBorder + r] += Z[(size_t)r * np + i] * w;
-    }
-    if (i < nV) {
-#pragma unroll
-      for (int r = 0; r < kProjMaxBorder; ++r)
-        if (r < nb) {
-          const double* rv = rows + ((size_t)r * nV + i) * 3;
-          acc[r] += rv[0] * x[3 * i] + rv[1] * x[3 * i + 1] + rv[2] * x[3 * i + 2];
-        }
+        if (r < nb) acc[kProjMaxBorder + r] += d.Z[(size_t)r * np + i] * w;
     }
   }
-  __shared__ double sred[4][kProjSlots];
-  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  // border dot products over the vertices, spread over the workgroups
+  for (int i = blk * kSpThreads + t; i < nV; i += gridDim.x * kSpThreads) {
+#pragma unroll
+    for (int r = 0; r < kProjMaxBorder; ++r)
+      if (r < nb) {
+        const double* rv = d.rows + ((size_t)r * nV + i) * 3;
+        acc[r] += rv[0] * x[3 * i] + rv[1] * x[3 * i + 1] + rv[2] * x[3 * i + 2];
+      }
+  }
+  if (np > 0) {
+    tri_local_solve(d.lo, d.uinv, d.tc, L, blk, v, wa, wb);
+#pragma unroll
+    for (int j = 0; j < kSpMaxM; ++j)
+      if (j < cnt) d.g[k0 + j] = v[j];
+  }
+  const int lane = t % 64, w = t / 64;
 #pragma unroll
   for (int q = 0; q < kProjSlots; ++q) {
     if ((q % kProjMaxBorder) >= nb) continue;  // unused slot (uniform)
-    double v = acc[q];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) sred[w][q] = v;
+    double s = acc[q];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) sred[w][q] = s;
   }
   __syncthreads();
-  if (threadIdx.x < kProjSlots) {
-    const int q = threadIdx.x;
-    part[(size_t)blockIdx.x * kProjSlots + q] =
+  if (t < kProjSlots) {
+    const int q = t;
+    d.part[(size_t)blk * kProjSlots + q] =
         (q % kProjMaxBorder) < nb ? ((sred[0][q] + sred[1][q]) + sred[2][q]) + sred[3][q] : 0.0;
   }
 }
 
-__global__ __launch_bounds__(kTriThreads) void k_proj_solve(const double* __restrict__ part, int nblk, int nb,
-                                                           const double* __restrict__ Sinv,
-                                                           const double* __restrict__ lo,
-                                                           const double* __restrict__ uinv,
-                                                           const double* __restrict__ tc,
-                                                           const double* __restrict__ wp, double* __restrict__ yp,
-                                                           double* __restrict__ yb, int np) {
-  __shared__ double wa[kTriWaves], wbs[kTriWaves];
+__global__ __launch_bounds__(kSpThreads) void k_proj_solve(const ProjData d, int nblk) {
   __shared__ double tot[kProjSlots];
-  const int t = threadIdx.x, lane = t % 64;
-  {  // wave q sums slot q over the workgroups of k_proj_rows
-    const int q = t / 64;
-    double v = (lane < nblk && (q % kProjMaxBorder) < nb) ? part[(size_t)lane * kProjSlots + q] : 0.0;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) tot[q] = v;
+  __shared__ double rhs[2 * (kSpMaxB - 1)];
+  const int t = threadIdx.x, nb = d.nb;
+  {  // slot q = t / 16 summed over the workgroups of k_proj_rows by 16 lanes
+    const int q = t / 16, sgm = t % 16;
+    double v = 0.0;
+    if ((q % kProjMaxBorder) < nb)
+      for (int k = sgm; k < nblk; k += 16) v += d.part[(size_t)k * kProjSlots + q];
+    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (sgm == 0) tot[q] = v;
+  }
+  const TriBlocks& L = d.tri;
+  const int nr = L.nr;
+  for (int i = t; i < nr; i += kSpThreads) {
+    const int q = i / 2;
+    rhs[i] = d.g[(i % 2 == 0) ? (q + 1) * L.S - 1 : (q + 1) * L.S];
   }
   __syncthreads();
   if (t < nb) {  // yb = S^-1 (wb - Z^T wp)
     double v = 0.0;
-    for (int j = 0; j < nb; ++j) v += Sinv[t * nb + j] * (tot[j] - tot[kProjMaxBorder + j]);
-    yb[t] = v;
+    for (int j = 0; j < nb; ++j) v += d.Sinv[t * nb + j] * (tot[j] - tot[kProjMaxBorder + j]);
+    d.yb[t] = v;
   }
-  if (np > 0) tridiag_solve_wg<true>(lo, uinv, tc, wp, yp, np, wa, wbs);
+  // U = M^-1 rhs: row i by two threads (halves of j), four independent partial sums each
+  __shared__ double half_sum[kSpThreads];
+  constexpr int kHalf = kSpThreads / 2;
+  const int jh = (nr + 1) / 2;
+  for (int i0 = 0; i0 < nr; i0 += kHalf) {
+    const int i = i0 + t % kHalf, h = t / kHalf;
+    const int j0 = h * jh, j1 = min(nr, j0 + jh);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (i < nr) {
+      const double* col = d.Rt + i;
+      int j = j0;
+      for (; j + 4 <= j1; j += 4) {
+        s0 += col[(size_t)j * nr] * rhs[j];
+        s1 += col[(size_t)(j + 1) * nr] * rhs[j + 1];
+        s2 += col[(size_t)(j + 2) * nr] * rhs[j + 2];
+        s3 += col[(size_t)(j + 3) * nr] * rhs[j + 3];
+      }
+      for (; j < j1; ++j) s0 += col[(size_t)j * nr] * rhs[j];
+    }
+    half_sum[t] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (h == 0 && i < nr) d.U[i] = half_sum[t] + half_sum[t + kHalf];
+    __syncthreads();
+  }
 }
 
 // out_v = in_v - [ sum_{path rows k at v} s(v) T_I (yp_k - (Z yb)_k) + sum_r yb[r] rows[r][v] ]
-__global__ __launch_bounds__(256) void k_apply_CT_z(const double* __restrict__ geo, const int* __restrict__ inc_off,
-                                                    const int* __restrict__ inc,
-                                                    const int* __restrict__ edge_path_row,
-                                                    const double* __restrict__ yp, const double* __restrict__ Z,
-                                                    int np, const double* __restrict__ rows,
-                                                    const double* __restrict__ yb, int nb, int nV,
-                                                    const double* __restrict__ in, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_apply_CT_z(const ProjData d, const double* __restrict__ in,
+                                                    double* __restrict__ out) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nV) return;
-  const int m = (np + kTriThreads - 1) / kTriThreads;
+  if (v >= d.nV) return;
+  const int np = d.np, nb = d.nb;
+  const TriBlocks& L = d.tri;
   double ybr[kProjMaxBorder];
 #pragma unroll
-  for (int r = 0; r < kProjMaxBorder; ++r) ybr[r] = r < nb ? yb[r] : 0.0;
+  for (int r = 0; r < kProjMaxBorder; ++r) ybr[r] = r < nb ? d.yb[r] : 0.0;
   double acc[3] = {0, 0, 0};
-  for (int k = inc_off[v]; k < inc_off[v + 1]; ++k) {
-    const int I = inc[k] >> 1;
-    const int pr = edge_path_row[I];
-    if (pr < 0) continue;
-    double y = yp[tri_chunk_pos(pr, m)];
+  auto add_row = [&](int pr, double c0, double c1, double c2) {
+    double y = d.g[pr];
+    const int q = pr / L.S;
+    if (q < L.B - 1) y -= d.V[pr] * d.U[2 * q + 1];
+    if (q > 0) y -= d.W[pr] * d.U[2 * (q - 1)];
 #pragma unroll
     for (int r = 0; r < kProjMaxBorder; ++r)
-      if (r < nb) y -= Z[(size_t)r * np + pr] * ybr[r];
-    const double sg = (inc[k] & 1) ? -1.0 : 1.0;
-    const double* g = geo + 8 * (size_t)I;
-    for (int cc = 0; cc < 3; ++cc) acc[cc] += sg * g[1 + cc] * y;
+      if (r < nb) y -= d.Z[(size_t)r * np + pr] * ybr[r];
+    acc[0] += c0 * y;
+    acc[1] += c1 * y;
+    acc[2] += c2 * y;
+  };
+  if (d.pvert) {
+    const ProjVert pv = d.pvert[v];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      if (pv.row[q] >= 0) add_row(pv.row[q], pv.c[q][0], pv.c[q][1], pv.c[q][2]);
+  } else {
+    for (int k = d.inc_off[v]; k < d.inc_off[v + 1]; ++k) {
+      const int I = d.inc[k] >> 1;
+      const int pr = d.edge_path_row[I];
+      if (pr < 0) continue;
+      const double sg = (d.inc[k] & 1) ? -1.0 : 1.0;
+      const double* g = d.geo + 8 * (size_t)I;
+      add_row(pr, sg * g[1], sg * g[2], sg * g[3]);
+    }
   }
 #pragma unroll
   for (int r = 0; r < kProjMaxBorder; ++r)
     if (r < nb)
-      for (int cc = 0; cc < 3; ++cc) acc[cc] += ybr[r] * rows[((size_t)r * nV + v) * 3 + cc];
+      for (int cc = 0; cc < 3; ++cc) acc[cc] += ybr[r] * d.rows[((size_t)r * d.nV + v) * 3 + cc];
   for (int cc = 0; cc < 3; ++cc) out[3 * v + cc] = in[3 * v + cc] - acc[cc];
 }
 
-void cons_project_fused(const double* geo, const int2* edges, const int* path_edge, int np, const double* rows,
-                        int nb, const double* Z, const double* Sinv, const double* lo_ch, const double* uinv_ch,
-                        const double* tc_ch, const int* inc_off, const int* inc, const int* edge_path_row, int nV,
-                        const double* in, double* out, double* part, double* wp_ch, double* yp_ch, double* yb,
-                        hipStream_t s) {
-  const int nblk = std::min(kProjBlocks, std::max(1, cdiv(std::max(np, nV), 256)));
-  hipLaunchKernelGGL(k_proj_rows, dim3(nblk), dim3(256), 0, s, geo, edges, path_edge, np, rows, nb, Z, nV, in,
-                     wp_ch, part);
-  hipLaunchKernelGGL(k_proj_solve, dim3(1), dim3(kTriThreads), 0, s, (const double*)part, nblk, nb, Sinv, lo_ch,
-                     uinv_ch, tc_ch, (const double*)wp_ch, yp_ch, yb, np);
-  hipLaunchKernelGGL(k_apply_CT_z, dim3(cdiv(nV, 256)), dim3(256), 0, s, geo, inc_off, inc, edge_path_row,
-                     (const double*)yp_ch, Z, np, rows, (const double*)yb, nb, nV, in, out);
+// The same projector in one workgroup and one launch for the coarse
+// multigrid levels (np, nV <= kTriThreads, so the path is one block; packed
+// rows and vertices), where three launches cost more than the work: thread t
+// owns path row t and vertex t.  Everything that does not depend on x is
+// loaded first; the partial sums are reduced in the workgroup, the
+// tridiagonal solve is one scan per direction with one row per thread, and
+// yp stays in LDS.
+__global__ __launch_bounds__(kTriThreads) void k_proj_small(const ProjData d, const double* __restrict__ x,
+                                                            double* __restrict__ out) {
+  __shared__ double yps[kTriThreads];
+  __shared__ double red[kTriWaves][kProjSlots];
+  __shared__ double tot[kProjSlots], ybs[kProjMaxBorder];
+  __shared__ double wa[kTriWaves], wbs[kTriWaves];
+  static_assert(kProjSlots == kTriWaves, "one slot per group of 16 lanes");
+  const int t = threadIdx.x, lane = t % 64, w = t / 64;
+  const int np = d.np, nV = d.nV, nb = d.nb;
+  const bool row = t < np, vert = t < nV;
+  ProjRow pr_t;
+  double l_t = 0.0, ui_t = 0.0, c_t = 0.0;
+  if (row) {
+    pr_t = d.prow[t];
+    l_t = d.lo[t];
+    ui_t = d.uinv[t];
+    c_t = d.tc[t];
+  }
+  ProjVert pv;
+  pv.row[0] = pv.row[1] = -1;
+  if (vert) pv = d.pvert[t];
+  double acc[kProjSlots];
+#pragma unroll
+  for (int q = 0; q < kProjSlots; ++q) acc[q] = 0.0;
+  double wv = 0.0;
+  if (row) {
+    const int a = pr_t.ends.x, b = pr_t.ends.y;
+    wv = pr_t.t[0] * (x[3 * a] - x[3 * b]) + pr_t.t[1] * (x[3 * a + 1] - x[3 * b + 1]) +
+         pr_t.t[2] * (x[3 * a + 2] - x[3 * b + 2]);
+#pragma unroll
+    for (int r = 0; r < kProjMaxBorder; ++r)
+      if (r < nb) acc[kProjMaxBorder + r] = d.Z[(size_t)r * np + t] * wv;
+  }
+  const double x0 = vert ? x[3 * t] : 0.0, x1 = vert ? x[3 * t + 1] : 0.0, x2 = vert ? x[3 * t + 2] : 0.0;
+  if (vert) {
+#pragma unroll
+    for (int r = 0; r < kProjMaxBorder; ++r)
+      if (r < nb) {
+        const double* rv = d.rows + ((size_t)r * nV + t) * 3;
+        acc[r] = rv[0] * x0 + rv[1] * x1 + rv[2] * x2;
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < kProjSlots; ++q) {
+    if ((q % kProjMaxBorder) >= nb) continue;  // unused slot (uniform)
+    double v = acc[q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[w][q] = v;
+  }
+  __syncthreads();
+  if (t < kTriWaves * kProjSlots) {  // slot q = t / 16 summed over the 16 waves by 16 lanes
+    const int q = t / kTriWaves, ww = t % kTriWaves;
+    double v = (q % kProjMaxBorder) < nb ? red[ww][q] : 0.0;
+    for (int off = kTriWaves / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (ww == 0) tot[q] = v;
+  }
+  __syncthreads();
+  if (t < nb) {  // yb = S^-1 (wb - Z^T wp)
+    double v = 0.0;
+    for (int j = 0; j < nb; ++j) v += d.Sinv[t * nb + j] * (tot[j] - tot[kProjMaxBorder + j]);
+    ybs[t] = v;
+  }
+  if (np > 0) {
+    // forward z = b - l z_prev, then backward y = (z - c y_next) / u, one row per thread
+    double A = row ? -l_t : 1.0, B = row ? wv : 0.0;
+    scan_compose<kTriWaves>(A, B, false, wa, wbs);
+    const double z = row ? -l_t * B + wv : 0.0;
+    __syncthreads();  // the LDS slots are reused by the second scan
+    A = row ? -c_t * ui_t : 1.0;
+    B = row ? z * ui_t : 0.0;
+    scan_compose<kTriWaves>(A, B, true, wa, wbs);
+    if (row) yps[t] = -c_t * ui_t * B + z * ui_t;
+  }
+  __syncthreads();
+  if (!vert) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int p = pv.row[q];
+    if (p < 0) continue;
+    double y = yps[p];
+#pragma unroll
+    for (int r = 0; r < kProjMaxBorder; ++r)
+      if (r < nb) y -= d.Z[(size_t)r * np + p] * ybs[r];
+    a0 += pv.c[q][0] * y;
+    a1 += pv.c[q][1] * y;
+    a2 += pv.c[q][2] * y;
+  }
+#pragma unroll
+  for (int r = 0; r < kProjMaxBorder; ++r)
+    if (r < nb) {
+      const double* rv = d.rows + ((size_t)r * nV + t) * 3;
+      a0 += ybs[r] * rv[0];
+      a1 += ybs[r] * rv[1];
+      a2 += ybs[r] * rv[2];
+    }
+  out[3 * t] = x0 - a0;
+  out[3 * t + 1] = x1 - a1;
+  out[3 * t + 2] = x2 - a2;
 }
 
-// Copies of the factors l, 1/u and the coupling c of an n-row tridiagonal
-// system in the chunk-transposed order of the one-workgroup solve.
-__global__ void k_tri_chunk(const double* __restrict__ lo, const double* __restrict__ uinv,
-                            const double* __restrict__ c, int n, double* __restrict__ lo_ch,
-                            double* __restrict__ uinv_ch, double* __restrict__ c_ch) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const int p = tri_chunk_pos(k, (n + kTriThreads - 1) / kTriThreads);
-  lo_ch[p] = lo[k];
-  uinv_ch[p] = uinv[k];
-  c_ch[p] = c[k];
+void cons_project_fused(const ProjData& d, const double* in, double* out, hipStream_t s) {
+  if (d.prow && d.pvert && d.np <= kTriThreads && d.nV <= kTriThreads && d.tri.B == 1) {
+    hipLaunchKernelGGL(k_proj_small, dim3(1), dim3(kTriThreads), 0, s, d, in, out);
+    return;
+  }
+  // one workgroup per block of path rows; at least enough for the vertices' border sums
+  const int nblk = std::max(d.np > 0 ? d.tri.B : 1, std::min(64, cdiv(d.nV, kSpThreads)));
+  hipLaunchKernelGGL(k_proj_rows, dim3(nblk), dim3(kSpThreads), 0, s, d, in);
+  hipLaunchKernelGGL(k_proj_solve, dim3(1), dim3(kSpThreads), 0, s, d, nblk);
+  hipLaunchKernelGGL(k_apply_CT_z, dim3(cdiv(d.nV, 256)), dim3(256), 0, s, d, in, out);
 }
 
-int tri_chunk_size(int n) { return n <= 0 ? 1 : cdiv(n, kTriThreads) * kTriThreads; }
+// Packed rows and vertices (vertex degree <= 2).
+__global__ void k_proj_pack(const double* __restrict__ geo, const int2* __restrict__ edges,
+                            const int* __restrict__ path_edge, int np, const int* __restrict__ inc_off,
+                            const int* __restrict__ inc, const int* __restrict__ edge_path_row, int nV,
+                            ProjRow* __restrict__ prow, ProjVert* __restrict__ pvert) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < np) {
+    const int I = path_edge[i];
+    const double* g = geo + 8 * (size_t)I;
+    ProjRow p;
+    p.t[0] = g[1];
+    p.t[1] = g[2];
+    p.t[2] = g[3];
+    p.ends = edges[I];
+    prow[i] = p;
+  }
+  if (i < nV) {
+    ProjVert pv;
+    int q = 0;
+    for (int k = inc_off[i]; k < inc_off[i + 1] && q < 2; ++k) {
+      const int I = inc[k] >> 1;
+      const int pr = edge_path_row[I];
+      if (pr < 0) continue;
+      const double sg = (inc[k] & 1) ? -1.0 : 1.0;
+      const double* g = geo + 8 * (size_t)I;
+      pv.row[q] = pr;
+      pv.c[q][0] = sg * g[1];
+      pv.c[q][1] = sg * g[2];
+      pv.c[q][2] = sg * g[3];
+      ++q;
+    }
+    for (; q < 2; ++q) {
+      pv.row[q] = -1;
+      pv.c[q][0] = pv.c[q][1] = pv.c[q][2] = 0.0;
+    }
+    pvert[i] = pv;
+  }
+}
 
-void tridiag_chunk_copy(const double* lo, const double* uinv, const double* c, int n, double* lo_ch,
-                        double* uinv_ch, double* c_ch, hipStream_t s) {
+void cons_project_pack(const double* geo, const int2* edges, const int* path_edge, int np, const int* inc_off,
+                       const int* inc, const int* edge_path_row, int nV, ProjRow* prow, ProjVert* pvert,
+                       hipStream_t s) {
+  const int n = std::max(np, nV);
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_tri_chunk, dim3(cdiv(n, 256)), dim3(256), 0, s, lo, uinv, c, n, lo_ch, uinv_ch, c_ch);
+  hipLaunchKernelGGL(k_proj_pack, dim3(cdiv(n, 256)), dim3(256), 0, s, geo, edges, path_edge, np, inc_off, inc,
+                     edge_path_row, nV, prow, pvert);
 }
 
 // ---------------------------------------------------------------------------

@@ -5,6 +5,7 @@
 #include <memory>
 #include <vector>
 
+#include "k_linalg.h"
 #include "rc_internal.h"
 
 namespace rc {
@@ -28,9 +29,14 @@ struct Cons {
   double *wp = nullptr, *yp = nullptr, *wb = nullptr, *yb = nullptr, *dots = nullptr, *rhs = nullptr;
   double* small = nullptr;
   double* part = nullptr;  // partial sums of the three-launch projector
-  // the three-launch projector's copies of the path factors and its work
-  // vectors, in the one-workgroup solve's chunk-transposed order
-  double *tri_ch = nullptr, *wp_ch = nullptr, *yp_ch = nullptr;
+  // block-partitioned path solve: partition, spikes (V then W), reduced
+  // inverse, and scratch (local solutions [max(nb, 1)][np], boundary values
+  // [max(nb, 1)][nr], right-hand sides of the spikes [2 np])
+  TriBlocks tri;
+  double *sp_VW = nullptr, *sp_Rt = nullptr, *sp_g = nullptr, *sp_U = nullptr, *sp_tmp = nullptr;
+  // packed path rows and vertices for the projector (vertex degree <= 2)
+  ProjRow* prow = nullptr;
+  ProjVert* pvert = nullptr;
 };
 
 // Dense FP64 saddle solve on one curve: H = Abar + C^T C (Cholesky),

@@ -192,9 +192,12 @@ void cons_free(Cons& k) {
   for (int* p : ip)
     if (p) hipFree(p);
   double* dp[] = {k.x0, k.len0, k.ones, k.geo, k.geo_eval, k.vals, k.rows, k.ta, k.td, k.tc, k.Kpb, k.Z, k.Sinv,
-                  k.tri_scratch, k.wp, k.yp, k.wb, k.yb, k.dots, k.rhs, k.small, k.part, k.tri_ch, k.wp_ch, k.yp_ch};
+                  k.tri_scratch, k.wp, k.yp, k.wb, k.yb, k.dots, k.rhs, k.small, k.part, k.sp_VW, k.sp_Rt, k.sp_g,
+                  k.sp_U, k.sp_tmp};
   for (double* p : dp)
     if (p) hipFree(p);
+  if (k.prow) hipFree(k.prow);
+  if (k.pvert) hipFree(k.pvert);
   k = Cons();
 }
 
@@ -261,10 +264,22 @@ rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask) {
   RC_TRY(dalloc(&k.rhs, std::max(k.nb, 1)));
   RC_TRY(dalloc(&k.dots, (size_t)std::max(k.nb * k.nb, 4)));
   RC_TRY(dalloc(&k.small, (size_t)std::max(k.nb * k.nb, 8)));
-  RC_TRY(dalloc(&k.part, (size_t)64 * 2 * kProjMaxBorder));
-  RC_TRY(dalloc(&k.tri_ch, 3 * (size_t)tri_chunk_size(k.np)));
-  RC_TRY(dalloc(&k.wp_ch, tri_chunk_size(k.np)));
-  RC_TRY(dalloc(&k.yp_ch, tri_chunk_size(k.np)));
+  k.tri = tri_blocks(k.np);
+  if (k.tri.B > kSpMaxB) {
+    set_error("edge-length constraints: too many path rows for the block-partitioned solve");
+    return RC_ERR_UNSUPPORTED;
+  }
+  const size_t nbc = std::max(k.nb, 1), npc = std::max(k.np, 1);
+  RC_TRY(dalloc(&k.part, (size_t)std::max(k.tri.B, 64) * 2 * kProjMaxBorder));
+  RC_TRY(dalloc(&k.sp_VW, 2 * npc));
+  RC_TRY(dalloc(&k.sp_Rt, std::max((size_t)k.tri.nr * k.tri.nr, (size_t)1)));
+  RC_TRY(dalloc(&k.sp_g, nbc * npc));
+  RC_TRY(dalloc(&k.sp_U, nbc * std::max(k.tri.nr, 1)));
+  RC_TRY(dalloc(&k.sp_tmp, 2 * npc));
+  if (cv.max_degree <= 2) {
+    RC_HIP(hipMalloc(&k.prow, sizeof(ProjRow) * std::max(k.np, 1)));
+    RC_HIP(hipMalloc(&k.pvert, sizeof(ProjVert) * std::max(nV, 1)));
+  }
   std::vector<double> ones(nE, 1.0);
   RC_HIP(hipMemcpy(k.ones, ones.data(), sizeof(double) * nE, hipMemcpyHostToDevice));
   RC_HIP(hipMemset(k.x0, 0, sizeof(double) * 3));
@@ -294,6 +309,19 @@ rc_status cons_set_targets(rc_ctx* c, const double* gamma_ref, const double* x0_
   return sync(c);
 }
 
+// The path block's factors as a block-partitioned tridiagonal system.
+static TriSys path_sys(const Cons& k) {
+  TriSys T;
+  T.L = k.tri;
+  T.lo = k.tri_scratch;
+  T.uinv = k.tri_scratch + k.np;
+  T.c = k.tc;
+  T.V = k.sp_VW;
+  T.W = k.sp_VW + k.np;
+  T.Rt = k.sp_Rt;
+  return T;
+}
+
 // C(gamma), the tridiagonal path block and the border Schur complement.
 rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma) {
   if (k.k == 0) return RC_OK;
@@ -308,7 +336,7 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma)
   int* tinfo = (int*)(k.tri_scratch + 2 * np);
   if (np > 0) {
     cons_path_coeffs(k.geo, cv.edges, k.path_edge, k.path_prev, np, k.ta, k.td, k.tc, s);
-    tridiag_factor(k.ta, k.td, k.tc, np, lo, uinv, tinfo, s);
+    tri_prepare(k.ta, k.td, k.tc, k.tri, lo, uinv, k.sp_VW, k.sp_Rt, k.sp_tmp, tinfo, s);
     int info = 0;
     RC_HIP(hipMemcpyAsync(&info, tinfo, sizeof(int), hipMemcpyDeviceToHost, s));
     RC_TRY(sync(c));
@@ -316,16 +344,15 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma)
       set_error("edge-length constraint Gram matrix is not positive definite");
       return RC_ERR_SINGULAR;
     }
-    const size_t nc = tri_chunk_size(np);
-    tridiag_chunk_copy(lo, uinv, k.tc, np, k.tri_ch, k.tri_ch + nc, k.tri_ch + 2 * nc, s);
   }
+  if (k.prow)
+    cons_project_pack(k.geo, cv.edges, k.path_edge, np, cv.inc_off, cv.inc, k.edge_path_row, nV, k.prow, k.pvert, s);
   if (nb > 0) {
     for (int r = 0; r < nb; ++r)
       vec_dots(k.rows, 3 * nV, k.rows + (size_t)r * 3 * nV, 0, 3 * nV, nb, c->red, k.dots + r * nb, s);
     if (np > 0) {
       cons_path_apply(k.geo, cv.edges, k.path_edge, np, k.rows, nV, nb, k.Kpb, s);
-      for (int r = 0; r < nb; ++r)
-        tridiag_solve(lo, uinv, k.tc, k.Kpb + (size_t)r * np, k.Z + (size_t)r * np, np, s);
+      tri_solve(path_sys(k), k.Kpb, np, k.Z, np, nb, k.sp_g, k.sp_U, s);
       for (int r = 0; r < nb; ++r) vec_dots(k.Kpb, np, k.Z + (size_t)r * np, 0, np, nb, c->red, k.small + r * nb, s);
     }
     std::vector<double> S(nb * nb), kz(nb * nb, 0.0);
@@ -344,7 +371,7 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma)
 // (wp, wb) -> (yp, yb) = (C C^T)^-1 w
 static void cons_solve_K(rc_ctx* c, Cons& k) {
   hipStream_t s = c->stream;
-  if (k.np > 0) tridiag_solve(k.tri_scratch, k.tri_scratch + k.np, k.tc, k.wp, k.yp, k.np, s);
+  if (k.np > 0) tri_solve(path_sys(k), k.wp, k.np, k.yp, k.np, 1, k.sp_g, k.sp_U, s);
   if (k.nb > 0) {
     if (k.np > 0) vec_dots(k.Kpb, k.np, k.yp, 0, k.np, k.nb, c->red, k.dots, s);
     else hipMemsetAsync(k.dots, 0, sizeof(double) * k.nb, s);
@@ -362,10 +389,33 @@ void cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double*
     return;
   }
   if (k.nb <= kProjMaxBorder) {
-    const size_t nc = tri_chunk_size(k.np);
-    cons_project_fused(k.geo, cv.edges, k.path_edge, k.np, k.rows, k.nb, k.Z, k.Sinv, k.tri_ch, k.tri_ch + nc,
-                       k.tri_ch + 2 * nc, cv.inc_off, cv.inc, k.edge_path_row, nV, in, out, k.part, k.wp_ch,
-                       k.yp_ch, k.yb, s);
+    ProjData d;
+    d.np = k.np;
+    d.nb = k.nb;
+    d.nV = nV;
+    d.geo = k.geo;
+    d.edges = cv.edges;
+    d.path_edge = k.path_edge;
+    d.rows = k.rows;
+    d.Z = k.Z;
+    d.Sinv = k.Sinv;
+    d.tri = k.tri;
+    d.lo = k.tri_scratch;
+    d.uinv = k.tri_scratch + k.np;
+    d.tc = k.tc;
+    d.V = k.sp_VW;
+    d.W = k.sp_VW + k.np;
+    d.Rt = k.sp_Rt;
+    d.inc_off = cv.inc_off;
+    d.inc = cv.inc;
+    d.edge_path_row = k.edge_path_row;
+    d.prow = k.prow;
+    d.pvert = k.pvert;
+    d.part = k.part;
+    d.g = k.sp_g;
+    d.U = k.sp_U;
+    d.yb = k.yb;
+    cons_project_fused(d, in, out, s);
     return;
   }
   cons_path_apply(k.geo, cv.edges, k.path_edge, k.np, in, nV, 1, k.wp, s);
