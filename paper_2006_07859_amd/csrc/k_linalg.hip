@@ -182,9 +182,9 @@ void dense_cholesky(double* A, int n, int* info, hipStream_t s) {
   }
 }
 
-// L L^T X = B, B is n x m row-major; each workgroup owns up to 16
+// L L^T X = B, B is n x m row-major; each workgroup owns up to kSolveCols
 // right-hand-side columns.
-constexpr int kSolveCols = 16;
+constexpr int kSolveCols = 4;
 constexpr int kSolveRows = 32;  // row block of the blocked substitution
 
 // Blocked substitution: for each block of 32 rows, the block's triangular

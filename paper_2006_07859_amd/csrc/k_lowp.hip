@@ -153,8 +153,8 @@ __global__ __launch_bounds__(256) void k_assemble_lowp(
     const size_t tile = (size_t)rb * nkt + kt;
     tiles[tile * 64 + l] = vec;
     if (W32) {
-      tiles32[(tile * 64 + l) * 2] = make_float4(f[0], f[1], f[2], f[3]);
-      tiles32[(tile * 64 + l) * 2 + 1] = make_float4(f[4], f[5], f[6], f[7]);
+      tiles32[tile * 128 + l] = make_float4(f[0], f[1], f[2], f[3]);
+      tiles32[tile * 128 + 64 + l] = make_float4(f[4], f[5], f[6], f[7]);
     }
   }
   part[0][threadIdx.x] = rs;
@@ -315,7 +315,7 @@ __device__ __forceinline__ void b_values(const BSrc& s, double crg, float scale,
 // The loads for column tile kt + 1 are issued before the MFMAs of tile kt.
 // B operand: columns 0-2 hi, 3-5 lo parts of the three components.
 template <typename T, int RB>
-__global__ __launch_bounds__(256) void k_lowp_gemv(const typename Vec8<T>::type* __restrict__ tiles,
+__global__ __launch_bounds__(256, 4) void k_lowp_gemv(const typename Vec8<T>::type* __restrict__ tiles,
                                                    const float4* __restrict__ P, const float4* __restrict__ SQ,
                                                    const double* __restrict__ cref, const double* __restrict__ mx,
                                                    int n, int nrb, int nkt, int nsplit, int per,
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(256) void k_lowp_gemv(const typename Vec8<T>::type*
     V a[RB];
     BSrc bs = load_b(P, SQ, cref, k0, c, g);
 #pragma unroll
-    for (int r = 0; r < RB; ++r) a[r] = rows[r][(size_t)k0 * 64];
+    for (int r = 0; r < RB; ++r) a[r] = __builtin_nontemporal_load(&rows[r][(size_t)k0 * 64]);
     for (int kt = k0; kt < k1; ++kt) {
       V an[RB];
       BSrc bn;
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void k_lowp_gemv(const typename Vec8<T>::type*
       if (more) {
         bn = load_b(P, SQ, cref, kt + 1, c, g);
 #pragma unroll
-        for (int r = 0; r < RB; ++r) an[r] = rows[r][(size_t)(kt + 1) * 64];
+        for (int r = 0; r < RB; ++r) an[r] = __builtin_nontemporal_load(&rows[r][(size_t)(kt + 1) * 64]);
       }
       float bv[8];
       b_values(bs, crg, scale, bv);
@@ -385,9 +385,12 @@ __global__ __launch_bounds__(256) void k_lowp_gemv(const typename Vec8<T>::type*
 // FP32 version: a 16 x 32 tile is eight v_mfma_f32_16x16x4f32 products; in
 // product i lane l supplies A[l % 16][8 (l / 16) + i] and B row 8 (l / 16) + i
 // of column l % 16 (columns 0-2 used), so the eight products together contract
-// all 32 columns.
+// all 32 columns.  A tile is stored as two lane-contiguous halves (every
+// lane's entries 0-3, then every lane's entries 4-7), so each of the two
+// 16-byte loads of a wave covers whole cache lines; like the 16-bit tiles,
+// the FP32 tiles are read once per product with streaming (nontemporal) loads.
 template <int RB>
-__global__ __launch_bounds__(256) void k_lowp_gemv32(const float4* __restrict__ tiles, const float4* __restrict__ P,
+__global__ __launch_bounds__(256, 4) void k_lowp_gemv32(const float4* __restrict__ tiles, const float4* __restrict__ P,
                                                      const float4* __restrict__ SQ, const double* __restrict__ cref,
                                                      int n, int nrb, int nkt, int nsplit, int per,
                                                      float* __restrict__ part) {
@@ -406,14 +409,14 @@ __global__ __launch_bounds__(256) void k_lowp_gemv32(const float4* __restrict__ 
   for (int r = 0; r < RB; ++r) acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
   const float4* rows[RB];
 #pragma unroll
-  for (int r = 0; r < RB; ++r) rows[r] = tiles + ((size_t)min(rb0 + r, nrb - 1) * nkt * 64 + l) * 2;
+  for (int r = 0; r < RB; ++r) rows[r] = tiles + (size_t)min(rb0 + r, nrb - 1) * nkt * 128 + l;
   for (int kt = k0; kt < k1; ++kt) {
     const BSrc bs = load_b(P, SQ, cref, kt, c, g);
-    float4 a0[RB], a1[RB];
+    f32x4 a0[RB], a1[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      a0[r] = rows[r][(size_t)kt * 128];
-      a1[r] = rows[r][(size_t)kt * 128 + 1];
+      a0[r] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(&rows[r][(size_t)kt * 128]));
+      a1[r] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(&rows[r][(size_t)kt * 128 + 64]));
     }
     float b[8];
     b_values(bs, crg, 1.f, b);
@@ -493,6 +496,10 @@ __global__ __launch_bounds__(256) void k_lowp_finish(const float* __restrict__ p
 // host side
 // ---------------------------------------------------------------------------
 constexpr int kLowpRB = 4;  // row blocks per wave in the products (the reference group is 64 rows)
+// Waves per product launch (measured at 16k and 32k vertices: the streamed
+// 16-bit tiles reach the highest HBM rate with about 2,048 long-running waves,
+// the FP32 tiles with about 3,072).
+constexpr int kLowpWaves16 = 2048, kLowpWaves32 = 3072;
 
 rc_status LowpOp::ensure(const Curve& c, int fmt_, int band_, bool with32_) {
   if (!c.chain) {
@@ -516,10 +523,14 @@ rc_status LowpOp::ensure(const Curve& c, int fmt_, int band_, bool with32_) {
   nrb = cdiv(n, 16);
   nkt = cdiv(n, 32);
   ngroups = cdiv(nkt, 4);
+  // column tiles split so that each product launches about kLowpWaves16 (kLowpWaves32) waves
   const int nrg = cdiv(nrb, kLowpRB);
-  nsplit = std::max(1, std::min({32, nkt, cdiv(4096, nrg)}));
+  nsplit = std::max(1, std::min({64, nkt, cdiv(kLowpWaves16, nrg)}));
   per = cdiv(nkt, nsplit);
   nsplit = cdiv(nkt, per);
+  nsplit32 = std::max(1, std::min({64, nkt, cdiv(kLowpWaves32, nrg)}));
+  per32 = cdiv(nkt, nsplit32);
+  nsplit32 = cdiv(nkt, per32);
   const size_t nb = (size_t)2 * band;
   auto al = [](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 16)) == hipSuccess; };
   bool ok = al(&tiles, (size_t)nrb * nkt * 1024) && al((void**)&rowpart, sizeof(double) * (size_t)ngroups * n) &&
@@ -527,7 +538,7 @@ rc_status LowpOp::ensure(const Curve& c, int fmt_, int band_, bool with32_) {
             al((void**)&sigma, sizeof(double) * n) && al((void**)&bandpart, sizeof(double) * n) &&
             al((void**)&pbuf, sizeof(float) * 96 * (size_t)nkt) && al((void**)&sqdf, sizeof(float) * 32 * (size_t)nkt) &&
             al((void**)&cref, sizeof(double) * 3 * (size_t)nkt) &&
-            al((void**)&part, sizeof(float) * 3 * (size_t)n * nsplit) && al((void**)&mx, sizeof(double) * 2) &&
+            al((void**)&part, sizeof(float) * 3 * (size_t)n * std::max(nsplit, nsplit32)) && al((void**)&mx, sizeof(double) * 2) &&
             al((void**)&vinfo, sizeof(int4) * (size_t)n) && al((void**)&band_idx, sizeof(int) * nb * n) &&
             al((void**)&band_val, sizeof(float) * nb * n);
   if (ok && with32)
@@ -681,13 +692,13 @@ rc_status launch_lowp_apply32(const LowpOp& op, const double* X, double* Y, hipS
   }
   KernelTimer* t = (timer && timer->on) ? timer : nullptr;
   prep(op, X, s);
-  const int waves = cdiv(op.nrb, kLowpRB) * op.nsplit;
+  const int waves = cdiv(op.nrb, kLowpRB) * op.nsplit32;
   if (t) t->mark(t->asm32, s);
   hipLaunchKernelGGL((k_lowp_gemv32<kLowpRB>), dim3(cdiv(waves, 4)), dim3(256), 0, s, (const float4*)op.tiles32,
                      (const float4*)op.pbuf, (const float4*)op.sqdf, (const double*)op.cref, op.n, op.nrb, op.nkt,
-                     op.nsplit, op.per, op.part);
+                     op.nsplit32, op.per32, op.part);
   if (t) t->mark(t->asm32, s);
-  hipLaunchKernelGGL(k_lowp_finish, dim3(cdiv(op.n, 8)), dim3(256), 0, s, op.part, op.nsplit,
+  hipLaunchKernelGGL(k_lowp_finish, dim3(cdiv(op.n, 8)), dim3(256), 0, s, op.part, op.nsplit32,
                      (const double*)nullptr, op.band_idx, op.band_val, op.band, op.sigma32, op.sqd, X, op.n, Y);
   RC_HIP(hipGetLastError());
   return RC_OK;
