@@ -175,6 +175,196 @@ __global__ __launch_bounds__(256) void k_assemble_lowp(
   }
 }
 
+// The same tiles for curves (vertex degree <= 2) from edge pairs: an entry
+// S^_vw sums over the edges I at v and J at w, and each edge pair serves up
+// to four entries, so the workgroup evaluates every distinct (row edge,
+// column edge) pair of a 16 x 32 tile once into LDS (the distinct edges of
+// the rows and of the columns found by ballots), forms the 512 entries from
+// the table, and the owning wave stores its lane vectors.  The pair terms are
+// evaluated with the smaller edge first and an entry sums its terms with the
+// smaller vertex's edges outermost, so that S^ is exactly symmetric.
+template <typename T, int EC, bool W32>
+__global__ __launch_bounds__(256) void k_assemble_lowp_ep(
+    const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB, const V4<double>* __restrict__ GT,
+    const int2* __restrict__ edges, const int* __restrict__ inc_off, const int* __restrict__ inc,
+    const double* __restrict__ edge_out, const double* __restrict__ sqd, const int4* __restrict__ vinfo, int band,
+    int n, int nkt, float half_expo, typename Vec8<T>::type* __restrict__ tiles, float4* __restrict__ tiles32,
+    double* __restrict__ rowpart, double* __restrict__ rowpart32) {
+  __shared__ int rE[16][2], cE[32][2];       // incident edge per (vertex, slot), -1: none
+  __shared__ float rS[16][2], cS[32][2];     // its sign s(v)
+  __shared__ int rI[16][2], cI[32][2];       // index in the distinct list
+  __shared__ int rlist[32], clist[64], nlist[2];
+  __shared__ float G[32][65], H[32][65];     // pair terms rho T_I.T_J and l_I l_J rho0
+  __shared__ float E[16][33];                // the tile's entries
+  __shared__ double part[2][256];
+  const int rb = blockIdx.x, t = threadIdx.x, wave = t / 64, l = t % 64;
+  // slots of the 16 row vertices (threads 0-31) and distinct row edges
+  auto slot = [&](int v, int sl, int& e, float& sg) {
+    e = -1;
+    sg = 0.f;
+    if (v < n) {
+      const int kk = inc_off[v] + sl;
+      if (kk < inc_off[v + 1]) {
+        e = inc[kk] >> 1;
+        sg = (inc[kk] & 1) ? 1.f : -1.f;
+      }
+    }
+  };
+  if (t < 32) slot(rb * 16 + t / 2, t % 2, rE[t / 2][t % 2], rS[t / 2][t % 2]);
+  __syncthreads();
+  if (wave == 0) {  // lanes 0-31: a slot is new if no earlier slot has its edge
+    const int k = l;
+    const int e = k < 32 ? rE[k / 2][k % 2] : -1;
+    bool fresh = e >= 0;
+    for (int q = 0; q < k && fresh; ++q)
+      if (rE[q / 2][q % 2] == e) fresh = false;
+    const unsigned long long bal = __ballot(fresh);
+    if (fresh) rlist[__popcll(bal & ((1ull << k) - 1ull))] = e;
+    if (k == 0) nlist[0] = __popcll(bal);
+  }
+  __syncthreads();
+  if (t < 32) {  // each slot's index in the list
+    const int e = rE[t / 2][t % 2];
+    int idx = -1;
+    for (int q = 0; q < nlist[0] && e >= 0; ++q)
+      if (rlist[q] == e) idx = q;
+    rI[t / 2][t % 2] = idx;
+  }
+  double rs = 0.0, rs32 = 0.0;
+  const int nr = nlist[0];
+  for (int q = 0; q < 4; ++q) {
+    const int kt = blockIdx.y * 4 + q;
+    if (kt >= nkt) break;  // uniform
+    if (t < 64) slot(kt * 32 + t / 2, t % 2, cE[t / 2][t % 2], cS[t / 2][t % 2]);
+    __syncthreads();
+    if (wave == 0) {
+      const int e = cE[l / 2][l % 2];
+      bool fresh = e >= 0;
+      for (int p = 0; p < l && fresh; ++p)
+        if (cE[p / 2][p % 2] == e) fresh = false;
+      const unsigned long long bal = __ballot(fresh);
+      if (fresh) clist[__popcll(bal & ((1ull << l) - 1ull))] = e;
+      if (l == 0) nlist[1] = __popcll(bal);
+    }
+    __syncthreads();
+    const int nc = nlist[1];
+    if (t < 64) {
+      const int e = cE[t / 2][t % 2];
+      int idx = -1;
+      for (int p = 0; p < nc && e >= 0; ++p)
+        if (clist[p] == e) idx = p;
+      cI[t / 2][t % 2] = idx;
+    }
+    for (int p = t; p < nr * nc; p += 256) {
+      const int a = p / nc, b = p % nc;
+      int I = rlist[a], J = clist[b];
+      float g = 0.f, h = 0.f;
+      const int2 ei = edges[I], ej = edges[J];
+      if (I != J && ei.x != ej.x && ei.x != ej.y && ei.y != ej.x && ei.y != ej.y) {
+        if (I > J) {  // the smaller edge first
+          const int tmp = I;
+          I = J;
+          J = tmp;
+        }
+        const V4<double> ia = GA[I], ib = GB[I], td = GT[I], ja = GA[J], jb = GB[J], tjd = GT[J];
+        const float tix = (float)td.x, tiy = (float)td.y, tiz = (float)td.z;
+        const float tjx = (float)tjd.x, tjy = (float)tjd.y, tjz = (float)tjd.z;
+        float rho = 0.f, rho0 = 0.f;
+        const V4<double>* P[2] = {&ia, &ib};
+        const V4<double>* Q[2] = {&ja, &jb};
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+            const float dx = (float)(P[x]->x - Q[y]->x), dy = (float)(P[x]->y - Q[y]->y),
+                        dz = (float)(P[x]->z - Q[y]->z);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float rs_ = f_rsq<float>(r2), ri = rs_ * rs_;
+            const float pw = pow_sigma<EC, float>(r2, rs_, ri, half_expo);
+            rho += pw;
+            rho0 += pw * (cross_norm2<float>(tix, tiy, tiz, dx, dy, dz) + cross_norm2<float>(tjx, tjy, tjz, dx, dy, dz)) *
+                    ri * ri;
+          }
+        g = rho * (tix * tjx + tiy * tjy + tiz * tjz);
+        h = (float)ia.w * (float)ja.w * rho0;
+      }
+      G[a][b] = g;
+      H[a][b] = h;
+    }
+    __syncthreads();
+    for (int p = t; p < 16 * 32; p += 256) {  // the tile's entries
+      const int vl = p / 32, wl = p % 32;
+      const int v = rb * 16 + vl, w = kt * 32 + wl;
+      float sf = 0.f;
+      if (v < n && w < n && v != w) {
+        const int off = chain_offset(vinfo[v], vinfo[w]);
+        if (off < -band || off > band) {
+          float acc = 0.f;
+          auto term = [&](int su, int sw) {
+            const int I = rE[vl][su], J = cE[wl][sw];
+            if (I < 0 || J < 0) return;
+            if (I == J) {  // v and w are the two ends of edge I
+              const double* o = edge_out + 8 * (size_t)I;  // (Wq, P0) in slots 0, 1
+              const double le = GA[I].w;
+              acc += (float)(-o[0] / (2.0 * le) + le * o[1] / 16.0);
+              return;
+            }
+            const int a = rI[vl][su], b = cI[wl][sw];
+            acc += -0.5f * rS[vl][su] * cS[wl][sw] * G[a][b] - 0.0625f * H[a][b];
+          };
+          if (v < w) {
+            term(0, 0); term(0, 1); term(1, 0); term(1, 1);
+          } else {
+            term(0, 0); term(1, 0); term(0, 1); term(1, 1);
+          }
+          sf = (float)((double)acc / (sqd[v] * sqd[w]));
+        }
+      }
+      E[vl][wl] = sf;
+    }
+    __syncthreads();
+    if (wave == q) {  // the owning wave stores its lane vectors
+      typename Vec8<T>::type vec;
+      float f[8];
+      const int vl = l % 16, w0 = kt * 32 + 8 * (l / 16);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float sf = E[vl][8 * (l / 16) + j];
+        const T r = (T)sf;
+        vec[j] = r;
+        f[j] = sf;
+        if (sf != 0.f) {
+          const double sw = sqd[w0 + j];
+          rs += (double)(float)r * sw;
+          rs32 += (double)sf * sw;
+        }
+      }
+      const size_t tile = (size_t)rb * nkt + kt;
+      tiles[tile * 64 + l] = vec;
+      if (W32) {
+        tiles32[tile * 128 + l] = make_float4(f[0], f[1], f[2], f[3]);
+        tiles32[tile * 128 + 64 + l] = make_float4(f[4], f[5], f[6], f[7]);
+      }
+    }
+  }
+  part[0][t] = rs;
+  part[1][t] = rs32;
+  __syncthreads();
+  if (t < 16) {
+    // row t appears in lanes t + 16 g (g < 4) of each of the 4 waves
+    double a16 = 0.0, a32 = 0.0;
+    for (int q = 0; q < 16; ++q) {
+      a16 += part[0][q * 16 + t];
+      a32 += part[1][q * 16 + t];
+    }
+    const int vv = rb * 16 + t;
+    if (vv < n) {
+      rowpart[(size_t)blockIdx.y * n + vv] = a16;
+      if (W32) rowpart32[(size_t)blockIdx.y * n + vv] = a32;
+    }
+  }
+}
+
 // FP32 band: entries (v, w) with w at canonical chain offset o, 0 < |o| <= band,
 // computed in FP64.  band_idx / band_val are [n][2 band]; slot o - 1 holds
 // offset o > 0 and slot band - o - 1 offset o < 0; band_idx is -1 where the
@@ -606,7 +796,15 @@ template <typename T, int EC>
 static void assemble_t(const Curve& c, LowpOp& op, float half_expo, hipStream_t s) {
   typedef typename Vec8<T>::type V;
   dim3 grid(op.nrb, op.ngroups);
-  if (op.with32)
+  if (c.max_degree <= 2 && op.with32)
+    hipLaunchKernelGGL((k_assemble_lowp_ep<T, EC, true>), grid, dim3(256), 0, s, c.gd.a, c.gd.b, c.gd.t, c.edges,
+                       c.inc_off, c.inc, c.edge_out, op.sqd, op.vinfo, op.band, op.n, op.nkt, half_expo,
+                       (V*)op.tiles, (float4*)op.tiles32, op.rowpart, op.rowpart32);
+  else if (c.max_degree <= 2)
+    hipLaunchKernelGGL((k_assemble_lowp_ep<T, EC, false>), grid, dim3(256), 0, s, c.gd.a, c.gd.b, c.gd.t, c.edges,
+                       c.inc_off, c.inc, c.edge_out, op.sqd, op.vinfo, op.band, op.n, op.nkt, half_expo,
+                       (V*)op.tiles, (float4*)nullptr, op.rowpart, (double*)nullptr);
+  else if (op.with32)
     hipLaunchKernelGGL((k_assemble_lowp<T, EC, true>), grid, dim3(256), 0, s, c.gd.a, c.gd.b, c.gd.t, c.edges,
                        c.inc_off, c.inc, c.edge_out, op.sqd, op.vinfo, op.band, op.n, op.nkt, half_expo,
                        (V*)op.tiles, (float4*)op.tiles32, op.rowpart, op.rowpart32);

@@ -874,6 +874,12 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
   bool converged = false;
   const bool watch = o.fallback_after > 0 && (o.solver == RC_SOLVE_PCG_MULTILEVEL || o.solver == RC_SOLVE_PCG_LEARNED);
   int growing = 0;  // consecutive iterations with a growing recurrence residual
+  // with an inexact Krylov operator (FP32 block or FP32 pairs) a sweep ends
+  // early when its recurrence residual stalls at the operator's floor (less
+  // than halved over 5 iterations): the next sweep restarts from the FP64
+  // true residual
+  const bool inexact = (lowp && c->lowp_outer == 1 && o.lowp_outer == 1) || op != RC_F64;
+  double window[6];
   while (it < o.max_iter && !converged) {
     RC_TRY(precondition(c, o.solver, r, z));
     vec_copy(z, p, n3, s);
@@ -902,6 +908,8 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
       const double res_prev = res;
       res = std::sqrt(rr) / bn;
       if (trace_on()) fprintf(stderr, "[rc pcg] it %d rec-res %.3e\n", it, res);
+      const bool stalled = inexact && since > 5 && res > 0.5 * window[(since - 5) % 6];
+      window[since % 6] = res;
       growing = res > res_prev ? growing + 1 : 0;
       if (watch && growing >= o.fallback_after) {
         *iters_out = it;
@@ -909,7 +917,8 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
         set_error("projected PCG: the residual kept growing");
         return RC_ERR_NOT_CONVERGED;
       }
-      if (res < std::max(o.tol, o.inner_tol * res_sweep) || (o.replace_every > 0 && since >= o.replace_every)) {
+      if (res < std::max(o.tol, o.inner_tol * res_sweep) || (o.replace_every > 0 && since >= o.replace_every) ||
+          stalled) {
         // true residual r = P (b - Abar x) (FP64); restart the recurrence from it
         // a loose solve (tol >= 1e-4) checks with its own operator
         if (o.tol >= 1e-4) RC_TRY(apply_op(x, c->tmp));
