@@ -178,11 +178,19 @@ __global__ __launch_bounds__(256) void k_assemble_lowp(
 // The same tiles for curves (vertex degree <= 2) from edge pairs: an entry
 // S^_vw sums over the edges I at v and J at w, and each edge pair serves up
 // to four entries, so the workgroup evaluates every distinct (row edge,
-// column edge) pair of a 16 x 32 tile once into LDS (the distinct edges of
-// the rows and of the columns found by ballots), forms the 512 entries from
-// the table, and the owning wave stores its lane vectors.  The pair terms are
-// evaluated with the smaller edge first and an entry sums its terms with the
-// smaller vertex's edges outermost, so that S^ is exactly symmetric.
+// column edge) pair of a 16 x 32 tile once into LDS, forms the 512 entries
+// from the table, and the owning wave stores its lane vectors.  A vertex's
+// incident edge is a repeat within the tile when its other end is an earlier
+// vertex of the same tile, so the distinct edges are found by one ballot; the
+// edges' geometry and the vertices' data are staged in LDS.  The pair terms
+// are evaluated with the smaller edge first and an entry sums its terms with
+// the smaller vertex's edges outermost, so that S^ is exactly symmetric.
+struct EpEdge {
+  double a[3], b[3];  // end points
+  float t[3], l;      // unit tangent, length
+  float dg;           // the term of an entry whose two vertices are the ends of this edge
+};
+
 template <typename T, int EC, bool W32>
 __global__ __launch_bounds__(256) void k_assemble_lowp_ep(
     const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB, const V4<double>* __restrict__ GT,
@@ -190,103 +198,101 @@ __global__ __launch_bounds__(256) void k_assemble_lowp_ep(
     const double* __restrict__ edge_out, const double* __restrict__ sqd, const int4* __restrict__ vinfo, int band,
     int n, int nkt, float half_expo, typename Vec8<T>::type* __restrict__ tiles, float4* __restrict__ tiles32,
     double* __restrict__ rowpart, double* __restrict__ rowpart32) {
-  __shared__ int rE[16][2], cE[32][2];       // incident edge per (vertex, slot), -1: none
-  __shared__ float rS[16][2], cS[32][2];     // its sign s(v)
-  __shared__ int rI[16][2], cI[32][2];       // index in the distinct list
-  __shared__ int rlist[32], clist[64], nlist[2];
-  __shared__ float G[32][65], H[32][65];     // pair terms rho T_I.T_J and l_I l_J rho0
-  __shared__ float E[16][33];                // the tile's entries
+  __shared__ int sE[2][32][2];      // [rows / columns][vertex][slot] incident edge, -1: none
+  __shared__ float sS[2][32][2];    // its sign s(v)
+  __shared__ int sI[2][32][2];      // index in the distinct list
+  __shared__ int slist[2][64], nlist[2];
+  __shared__ EpEdge ed[2][64];      // distinct row / column edges
+  __shared__ int4 vi[2][32];        // vinfo of the row / column vertices
+  __shared__ double sq[2][32];      // sqrt(d) of the row / column vertices
+  __shared__ float G[32][65], H[32][65];  // pair terms rho T_I.T_J and l_I l_J rho0
+  __shared__ float E[16][33];             // the tile's entries
   __shared__ double part[2][256];
   const int rb = blockIdx.x, t = threadIdx.x, wave = t / 64, l = t % 64;
-  // slots of the 16 row vertices (threads 0-31) and distinct row edges
-  auto slot = [&](int v, int sl, int& e, float& sg) {
-    e = -1;
-    sg = 0.f;
-    if (v < n) {
+  // slots of the side's nv vertices from v0 (threads 0 .. 2 nv - 1 of wave 0), distinct edges by ballot
+  auto side_setup = [&](int sd, int v0, int nv) {
+    int e = -1, u = -1;
+    float sg = 0.f;
+    const int vl = l / 2, sl = l % 2, v = v0 + vl;
+    if (wave == 0 && l < 2 * nv && v < n) {
       const int kk = inc_off[v] + sl;
       if (kk < inc_off[v + 1]) {
         e = inc[kk] >> 1;
         sg = (inc[kk] & 1) ? 1.f : -1.f;
+        const int2 ev = edges[e];
+        u = ev.x == v ? ev.y : ev.x;  // the edge's other end
       }
     }
+    if (wave == 0) {
+      const bool fresh = e >= 0 && !(u >= v0 && u < v);
+      const unsigned long long bal = __ballot(fresh);
+      const int idx = __popcll(bal & ((1ull << l) - 1ull));
+      if (l < 2 * nv) {
+        sE[sd][vl][sl] = e;
+        sS[sd][vl][sl] = sg;
+        sI[sd][vl][sl] = fresh ? idx : -1;
+      }
+      if (fresh) slist[sd][idx] = e;
+      if (l == 0) nlist[sd] = __popcll(bal);
+    }
+    __syncthreads();
+    if (wave == 0 && l < 2 * nv && e >= 0 && sI[sd][vl][sl] < 0) {  // a repeat takes the index at its other end
+      const int ul = u - v0;
+      sI[sd][vl][sl] = sE[sd][ul][0] == e ? sI[sd][ul][0] : sI[sd][ul][1];
+    }
+    if (t < nlist[sd]) {
+      const int I = slist[sd][t];
+      const V4<double> ga = GA[I], gb = GB[I], gt = GT[I];
+      EpEdge x;
+      x.a[0] = ga.x; x.a[1] = ga.y; x.a[2] = ga.z;
+      x.b[0] = gb.x; x.b[1] = gb.y; x.b[2] = gb.z;
+      x.t[0] = (float)gt.x; x.t[1] = (float)gt.y; x.t[2] = (float)gt.z;
+      x.l = (float)ga.w;
+      const double* o = edge_out + 8 * (size_t)I;  // (Wq, P0) in slots 0, 1
+      x.dg = (float)(-o[0] / (2.0 * ga.w) + ga.w * o[1] / 16.0);
+      ed[sd][t] = x;
+    }
+    if (t >= 128 && t < 128 + nv) {
+      const int v2 = v0 + (t - 128);
+      vi[sd][t - 128] = v2 < n ? vinfo[v2] : make_int4(-1, 0, 1, 0);
+      sq[sd][t - 128] = v2 < n ? sqd[v2] : 1.0;
+    }
+    __syncthreads();
   };
-  if (t < 32) slot(rb * 16 + t / 2, t % 2, rE[t / 2][t % 2], rS[t / 2][t % 2]);
-  __syncthreads();
-  if (wave == 0) {  // lanes 0-31: a slot is new if no earlier slot has its edge
-    const int k = l;
-    const int e = k < 32 ? rE[k / 2][k % 2] : -1;
-    bool fresh = e >= 0;
-    for (int q = 0; q < k && fresh; ++q)
-      if (rE[q / 2][q % 2] == e) fresh = false;
-    const unsigned long long bal = __ballot(fresh);
-    if (fresh) rlist[__popcll(bal & ((1ull << k) - 1ull))] = e;
-    if (k == 0) nlist[0] = __popcll(bal);
-  }
-  __syncthreads();
-  if (t < 32) {  // each slot's index in the list
-    const int e = rE[t / 2][t % 2];
-    int idx = -1;
-    for (int q = 0; q < nlist[0] && e >= 0; ++q)
-      if (rlist[q] == e) idx = q;
-    rI[t / 2][t % 2] = idx;
-  }
-  double rs = 0.0, rs32 = 0.0;
+  side_setup(0, rb * 16, 16);
   const int nr = nlist[0];
+  double rs = 0.0, rs32 = 0.0;
   for (int q = 0; q < 4; ++q) {
     const int kt = blockIdx.y * 4 + q;
     if (kt >= nkt) break;  // uniform
-    if (t < 64) slot(kt * 32 + t / 2, t % 2, cE[t / 2][t % 2], cS[t / 2][t % 2]);
-    __syncthreads();
-    if (wave == 0) {
-      const int e = cE[l / 2][l % 2];
-      bool fresh = e >= 0;
-      for (int p = 0; p < l && fresh; ++p)
-        if (cE[p / 2][p % 2] == e) fresh = false;
-      const unsigned long long bal = __ballot(fresh);
-      if (fresh) clist[__popcll(bal & ((1ull << l) - 1ull))] = e;
-      if (l == 0) nlist[1] = __popcll(bal);
-    }
-    __syncthreads();
+    side_setup(1, kt * 32, 32);
     const int nc = nlist[1];
-    if (t < 64) {
-      const int e = cE[t / 2][t % 2];
-      int idx = -1;
-      for (int p = 0; p < nc && e >= 0; ++p)
-        if (clist[p] == e) idx = p;
-      cI[t / 2][t % 2] = idx;
-    }
     for (int p = t; p < nr * nc; p += 256) {
       const int a = p / nc, b = p % nc;
-      int I = rlist[a], J = clist[b];
+      const int I = slist[0][a], J = slist[1][b];
       float g = 0.f, h = 0.f;
       const int2 ei = edges[I], ej = edges[J];
       if (I != J && ei.x != ej.x && ei.x != ej.y && ei.y != ej.x && ei.y != ej.y) {
-        if (I > J) {  // the smaller edge first
-          const int tmp = I;
-          I = J;
-          J = tmp;
-        }
-        const V4<double> ia = GA[I], ib = GB[I], td = GT[I], ja = GA[J], jb = GB[J], tjd = GT[J];
-        const float tix = (float)td.x, tiy = (float)td.y, tiz = (float)td.z;
-        const float tjx = (float)tjd.x, tjy = (float)tjd.y, tjz = (float)tjd.z;
+        const EpEdge& X = I < J ? ed[0][a] : ed[1][b];  // the smaller edge first
+        const EpEdge& Y = I < J ? ed[1][b] : ed[0][a];
         float rho = 0.f, rho0 = 0.f;
-        const V4<double>* P[2] = {&ia, &ib};
-        const V4<double>* Q[2] = {&ja, &jb};
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
           for (int y = 0; y < 2; ++y) {
-            const float dx = (float)(P[x]->x - Q[y]->x), dy = (float)(P[x]->y - Q[y]->y),
-                        dz = (float)(P[x]->z - Q[y]->z);
+            const double* P = x ? X.b : X.a;
+            const double* Q = y ? Y.b : Y.a;
+            const float dx = (float)(P[0] - Q[0]), dy = (float)(P[1] - Q[1]), dz = (float)(P[2] - Q[2]);
             const float r2 = dx * dx + dy * dy + dz * dz;
             const float rs_ = f_rsq<float>(r2), ri = rs_ * rs_;
             const float pw = pow_sigma<EC, float>(r2, rs_, ri, half_expo);
             rho += pw;
-            rho0 += pw * (cross_norm2<float>(tix, tiy, tiz, dx, dy, dz) + cross_norm2<float>(tjx, tjy, tjz, dx, dy, dz)) *
+            rho0 += pw * (cross_norm2<float>(X.t[0], X.t[1], X.t[2], dx, dy, dz) +
+                          cross_norm2<float>(Y.t[0], Y.t[1], Y.t[2], dx, dy, dz)) *
                     ri * ri;
           }
-        g = rho * (tix * tjx + tiy * tjy + tiz * tjz);
-        h = (float)ia.w * (float)ja.w * rho0;
+        g = rho * (X.t[0] * Y.t[0] + X.t[1] * Y.t[1] + X.t[2] * Y.t[2]);
+        h = X.l * Y.l * rho0;
       }
       G[a][b] = g;
       H[a][b] = h;
@@ -297,27 +303,26 @@ __global__ __launch_bounds__(256) void k_assemble_lowp_ep(
       const int v = rb * 16 + vl, w = kt * 32 + wl;
       float sf = 0.f;
       if (v < n && w < n && v != w) {
-        const int off = chain_offset(vinfo[v], vinfo[w]);
+        const int off = chain_offset(vi[0][vl], vi[1][wl]);
         if (off < -band || off > band) {
           float acc = 0.f;
           auto term = [&](int su, int sw) {
-            const int I = rE[vl][su], J = cE[wl][sw];
+            const int I = sE[0][vl][su], J = sE[1][wl][sw];
             if (I < 0 || J < 0) return;
+            const int a = sI[0][vl][su];
             if (I == J) {  // v and w are the two ends of edge I
-              const double* o = edge_out + 8 * (size_t)I;  // (Wq, P0) in slots 0, 1
-              const double le = GA[I].w;
-              acc += (float)(-o[0] / (2.0 * le) + le * o[1] / 16.0);
+              acc += ed[0][a].dg;
               return;
             }
-            const int a = rI[vl][su], b = cI[wl][sw];
-            acc += -0.5f * rS[vl][su] * cS[wl][sw] * G[a][b] - 0.0625f * H[a][b];
+            const int b = sI[1][wl][sw];
+            acc += -0.5f * sS[0][vl][su] * sS[1][wl][sw] * G[a][b] - 0.0625f * H[a][b];
           };
           if (v < w) {
             term(0, 0); term(0, 1); term(1, 0); term(1, 1);
           } else {
             term(0, 0); term(1, 0); term(0, 1); term(1, 1);
           }
-          sf = (float)((double)acc / (sqd[v] * sqd[w]));
+          sf = (float)((double)acc / (sq[0][vl] * sq[1][wl]));
         }
       }
       E[vl][wl] = sf;
@@ -326,15 +331,15 @@ __global__ __launch_bounds__(256) void k_assemble_lowp_ep(
     if (wave == q) {  // the owning wave stores its lane vectors
       typename Vec8<T>::type vec;
       float f[8];
-      const int vl = l % 16, w0 = kt * 32 + 8 * (l / 16);
+      const int vl = l % 16, c0 = 8 * (l / 16);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const float sf = E[vl][8 * (l / 16) + j];
+        const float sf = E[vl][c0 + j];
         const T r = (T)sf;
         vec[j] = r;
         f[j] = sf;
         if (sf != 0.f) {
-          const double sw = sqd[w0 + j];
+          const double sw = sq[1][c0 + j];
           rs += (double)(float)r * sw;
           rs32 += (double)sf * sw;
         }
