@@ -913,6 +913,7 @@ __global__ __launch_bounds__(256) void k_b_asm_assemble(const int4* __restrict__
 // streams 16-byte loads; the inputs are staged in LDS as FP32 differences to
 // the block's first row, so nearby columns keep their relative accuracy.
 constexpr int kAsmRows = 32, kAsmRowsWave = kAsmRows / 4;
+typedef float f4v __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_b_asm_apply(const int2* __restrict__ rb_items,
                                                      const int* __restrict__ inst_voff,
                                                      const long long* __restrict__ aoff, const float* __restrict__ A,
@@ -955,7 +956,8 @@ __global__ __launch_bounds__(256) void k_b_asm_apply(const int2* __restrict__ rb
 #pragma unroll
       for (int j = 0; j < kAsmRowsWave; ++j) {
         const int r = min(r0 + kAsmRowsWave * wave + j, n - 1);
-        av[j] = *(const float4*)(Ab + (size_t)r * ld + k);
+        const f4v a = __builtin_nontemporal_load((const f4v*)(Ab + (size_t)r * ld + k));  // read once per product
+        av[j] = make_float4(a.x, a.y, a.z, a.w);
       }
 #pragma unroll
       for (int j = 0; j < kAsmRowsWave; ++j) {
