@@ -49,7 +49,8 @@ void cons_border_rows(const double* geo, const int* inc_off, const int* inc, con
                       int nV, int bary, int total, const int* cut_edge, int ncut, double* rows, int nrows,
                       hipStream_t s);
 void cons_path_coeffs(const double* geo, const int2* edges, const int* path_edge, const int* path_prev, int np,
-                      double* ta, double* td, double* tc, hipStream_t s);
+                      const double* w, double* ta, double* td, double* tc, hipStream_t s);
+void cons_scale_rows(const double* rows, const double* w, int nV, int nrows, double* out, hipStream_t s);
 void cons_path_apply(const double* geo, const int2* edges, const int* path_edge, int np, const double* V, int nV,
                      int m, double* W, hipStream_t s);
 void cons_apply_CT(const double* geo, const int* inc_off, const int* inc, const int* edge_path_row,
@@ -89,6 +90,12 @@ struct ProjData {
   double* g = nullptr;              // block-local solution [np]
   double* U = nullptr;              // boundary values [nr]
   double* yb = nullptr;             // [nb]
+  // weighted form: with per-vertex weights w (C C^T above then being C W C^T),
+  // out = beta prev + scale M in with M = W - W C^T (C W C^T)^-1 C W, the
+  // inverse of W^-1 on the null space of C; w null: M = P
+  const double* w = nullptr;
+  double scale = 1.0, beta = 0.0;
+  const double* prev = nullptr;  // null: no beta term (prev may alias out)
 };
 void cons_project_fused(const ProjData& d, const double* in, double* out, hipStream_t s);
 void cons_project_pack(const double* geo, const int2* edges, const int* path_edge, int np, const int* inc_off,

@@ -756,27 +756,31 @@ void cons_border_rows(const double* geo, const int* inc_off, const int* inc, con
                        3 * bary + total, nV, rows);
 }
 
-// Tridiagonal coefficients of C_p C_p^T over the path rows (chain order):
-// diag 2, off-diagonal s_I(v) s_J(v) T_I.T_J for consecutive rows sharing v.
+// Tridiagonal coefficients of C_p W C_p^T over the path rows (chain order),
+// W = diag(w) per vertex (w null: the identity): diag w_i1 + w_i2 (|T_I| = 1),
+// off-diagonal s_I(v) s_J(v) w_v T_I.T_J for consecutive rows sharing v.
 __global__ void k_path_coeffs(const double* __restrict__ geo, const int2* __restrict__ edges,
                               const int* __restrict__ path_edge, const int* __restrict__ path_prev, int np,
-                              double* __restrict__ ta, double* __restrict__ td, double* __restrict__ tc) {
+                              const double* __restrict__ w, double* __restrict__ ta, double* __restrict__ td,
+                              double* __restrict__ tc) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= np) return;
-  td[k] = 2.0;
   const int I = path_edge[k];
+  const int2 ei = edges[I];
+  td[k] = w ? w[ei.x] + w[ei.y] : 2.0;
   if (path_prev[k]) {
     const int J = path_edge[k - 1];
-    int2 ei = edges[I], ej = edges[J];
+    const int2 ej = edges[J];
     // shared vertex and the signs (+1 at i1, -1 at i2)
     double si, sj;
-    if (ei.x == ej.x) { si = 1; sj = 1; }
-    else if (ei.x == ej.y) { si = 1; sj = -1; }
-    else if (ei.y == ej.x) { si = -1; sj = 1; }
-    else { si = -1; sj = -1; }
+    int sv;
+    if (ei.x == ej.x) { si = 1; sj = 1; sv = ei.x; }
+    else if (ei.x == ej.y) { si = 1; sj = -1; sv = ei.x; }
+    else if (ei.y == ej.x) { si = -1; sj = 1; sv = ei.y; }
+    else { si = -1; sj = -1; sv = ei.y; }
     const double* gi = geo + 8 * (size_t)I;
     const double* gj = geo + 8 * (size_t)J;
-    const double v = si * sj * (gi[1] * gj[1] + gi[2] * gj[2] + gi[3] * gj[3]);
+    const double v = si * sj * (gi[1] * gj[1] + gi[2] * gj[2] + gi[3] * gj[3]) * (w ? w[sv] : 1.0);
     ta[k] = v;
     tc[k - 1] = v;
   } else {
@@ -786,11 +790,25 @@ __global__ void k_path_coeffs(const double* __restrict__ geo, const int2* __rest
 }
 
 void cons_path_coeffs(const double* geo, const int2* edges, const int* path_edge, const int* path_prev, int np,
-                      double* ta, double* td, double* tc, hipStream_t s) {
+                      const double* w, double* ta, double* td, double* tc, hipStream_t s) {
   // tc[k-1] is written by row k; rows without a predecessor leave tc[k-1] to be zero
   hipMemsetAsync(tc, 0, sizeof(double) * np, s);
-  hipLaunchKernelGGL(k_path_coeffs, dim3(cdiv(np, 256)), dim3(256), 0, s, geo, edges, path_edge, path_prev, np,
+  hipLaunchKernelGGL(k_path_coeffs, dim3(cdiv(np, 256)), dim3(256), 0, s, geo, edges, path_edge, path_prev, np, w,
                      ta, td, tc);
+}
+
+// out[r][v][c] = rows[r][v][c] w[v] for nrows rows
+__global__ void k_scale_rows(const double* __restrict__ rows, const double* __restrict__ w, int nV, int nrows,
+                             double* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)nrows * nV * 3) return;
+  out[i] = rows[i] * w[(i / 3) % nV];
+}
+
+void cons_scale_rows(const double* rows, const double* w, int nV, int nrows, double* out, hipStream_t s) {
+  const size_t n = (size_t)nrows * nV * 3;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rows, w, nV, nrows, out);
 }
 
 // w[k] = C_{path_edge[k]} v = T_I . (v_i1 - v_i2), for m vectors (v_r = V + r*3nV, w_r = W + r*np).
@@ -920,6 +938,11 @@ __device__ __forceinline__ double proj_row_value(const ProjData& d, int i, const
     a = e.x;
     b = e.y;
   }
+  if (d.w) {  // C (W x)
+    const double wa = d.w[a], wb = d.w[b];
+    return t0 * (wa * x[3 * a] - wb * x[3 * b]) + t1 * (wa * x[3 * a + 1] - wb * x[3 * b + 1]) +
+           t2 * (wa * x[3 * a + 2] - wb * x[3 * b + 2]);
+  }
   return t0 * (x[3 * a] - x[3 * b]) + t1 * (x[3 * a + 1] - x[3 * b + 1]) + t2 * (x[3 * a + 2] - x[3 * b + 2]);
 }
 
@@ -950,11 +973,12 @@ __global__ __launch_bounds__(kSpThreads) void k_proj_rows(const ProjData d, cons
   }
   // border dot products over the vertices, spread over the workgroups
   for (int i = blk * kSpThreads + t; i < nV; i += gridDim.x * kSpThreads) {
+    const double wi = d.w ? d.w[i] : 1.0;
 #pragma unroll
     for (int r = 0; r < kProjMaxBorder; ++r)
       if (r < nb) {
         const double* rv = d.rows + ((size_t)r * nV + i) * 3;
-        acc[r] += rv[0] * x[3 * i] + rv[1] * x[3 * i + 1] + rv[2] * x[3 * i + 2];
+        acc[r] += wi * (rv[0] * x[3 * i] + rv[1] * x[3 * i + 1] + rv[2] * x[3 * i + 2]);
       }
   }
   if (np > 0) {
@@ -1071,7 +1095,11 @@ __global__ __launch_bounds__(256) void k_apply_CT_z(const ProjData d, const doub
   for (int r = 0; r < kProjMaxBorder; ++r)
     if (r < nb)
       for (int cc = 0; cc < 3; ++cc) acc[cc] += ybr[r] * d.rows[((size_t)r * d.nV + v) * 3 + cc];
-  for (int cc = 0; cc < 3; ++cc) out[3 * v + cc] = in[3 * v + cc] - acc[cc];
+  const double sw = d.scale * (d.w ? d.w[v] : 1.0);
+  for (int cc = 0; cc < 3; ++cc) {
+    const double o = sw * (in[3 * v + cc] - acc[cc]);
+    out[3 * v + cc] = d.prev ? d.beta * d.prev[3 * v + cc] + o : o;
+  }
 }
 
 // The same projector in one workgroup and one launch for the coarse
@@ -1108,19 +1136,21 @@ __global__ __launch_bounds__(kTriThreads) void k_proj_small(const ProjData d, co
   double wv = 0.0;
   if (row) {
     const int a = pr_t.ends.x, b = pr_t.ends.y;
-    wv = pr_t.t[0] * (x[3 * a] - x[3 * b]) + pr_t.t[1] * (x[3 * a + 1] - x[3 * b + 1]) +
-         pr_t.t[2] * (x[3 * a + 2] - x[3 * b + 2]);
+    const double wa = d.w ? d.w[a] : 1.0, wb = d.w ? d.w[b] : 1.0;
+    wv = pr_t.t[0] * (wa * x[3 * a] - wb * x[3 * b]) + pr_t.t[1] * (wa * x[3 * a + 1] - wb * x[3 * b + 1]) +
+         pr_t.t[2] * (wa * x[3 * a + 2] - wb * x[3 * b + 2]);
 #pragma unroll
     for (int r = 0; r < kProjMaxBorder; ++r)
       if (r < nb) acc[kProjMaxBorder + r] = d.Z[(size_t)r * np + t] * wv;
   }
   const double x0 = vert ? x[3 * t] : 0.0, x1 = vert ? x[3 * t + 1] : 0.0, x2 = vert ? x[3 * t + 2] : 0.0;
+  const double w_t = (vert && d.w) ? d.w[t] : 1.0;
   if (vert) {
 #pragma unroll
     for (int r = 0; r < kProjMaxBorder; ++r)
       if (r < nb) {
         const double* rv = d.rows + ((size_t)r * nV + t) * 3;
-        acc[r] = rv[0] * x0 + rv[1] * x1 + rv[2] * x2;
+        acc[r] = w_t * (rv[0] * x0 + rv[1] * x1 + rv[2] * x2);
       }
   }
 #pragma unroll
@@ -1177,9 +1207,17 @@ __global__ __launch_bounds__(kTriThreads) void k_proj_small(const ProjData d, co
       a1 += ybs[r] * rv[1];
       a2 += ybs[r] * rv[2];
     }
-  out[3 * t] = x0 - a0;
-  out[3 * t + 1] = x1 - a1;
-  out[3 * t + 2] = x2 - a2;
+  const double sw = d.scale * w_t;
+  const double o0 = sw * (x0 - a0), o1 = sw * (x1 - a1), o2 = sw * (x2 - a2);
+  if (d.prev) {
+    out[3 * t] = d.beta * d.prev[3 * t] + o0;
+    out[3 * t + 1] = d.beta * d.prev[3 * t + 1] + o1;
+    out[3 * t + 2] = d.beta * d.prev[3 * t + 2] + o2;
+  } else {
+    out[3 * t] = o0;
+    out[3 * t + 1] = o1;
+    out[3 * t + 2] = o2;
+  }
 }
 
 void cons_project_fused(const ProjData& d, const double* in, double* out, hipStream_t s) {

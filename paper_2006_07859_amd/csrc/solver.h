@@ -37,6 +37,7 @@ struct Cons {
   // packed path rows and vertices for the projector (vertex degree <= 2)
   ProjRow* prow = nullptr;
   ProjVert* pvert = nullptr;
+  double* rowsW = nullptr;  // W rows (weighted factors only)
 };
 
 // Dense FP64 saddle solve on one curve: H = Abar + C^T C (Cholesky),
@@ -53,6 +54,7 @@ struct Dense {
 struct Level {
   Curve curve;
   Cons cons;
+  Cons cons_w;             // the same constraints with C W C^T (the smoother's weighted projector)
   int* fine_of = nullptr;  // coarse vertex -> fine vertex index
   int2* prolong = nullptr; // fine vertex -> (coarse a, coarse b): value (x_a + x_b) / 2
   int *restr_off = nullptr, *restr_idx = nullptr;  // coarse vertex -> fine vertices that reference it
@@ -62,6 +64,7 @@ struct Level {
 
 struct MGLevelState {
   double *diag = nullptr, *x = nullptr, *b = nullptr, *r = nullptr, *d = nullptr, *t = nullptr, *pw = nullptr;
+  double* w = nullptr;  // 1 / diag (weighted smoother)
   double lmax = 0.0;
 };
 
@@ -126,6 +129,8 @@ struct rc_ctx {
   hipStream_t stream = nullptr;
   rc::Curve curve;
   rc::Cons cons;
+  rc::Cons cons_w;        // finest level's constraints with C W C^T (weighted smoother)
+  bool mg_weighted = false;  // smoothers use the weighted projector
   // FP64 work vectors [3 nV]
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *tmp = nullptr, *tmp2 = nullptr;
   double *diag = nullptr, *scal = nullptr, *red = nullptr, *trial = nullptr, *zmin = nullptr, *inc = nullptr;
@@ -167,7 +172,7 @@ bool trace_on();
 
 rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask);
 void cons_free(Cons& k);
-rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma);
+rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma, const double* w = nullptr);
 void cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double* out);
 void cons_values(rc_ctx* c, const double* gamma, double* phi);
 rc_status cons_set_targets(rc_ctx* c, const double* gamma_ref, const double* x0_h, double total_len0,

@@ -198,6 +198,7 @@ void cons_free(Cons& k) {
     if (p) hipFree(p);
   if (k.prow) hipFree(k.prow);
   if (k.pvert) hipFree(k.pvert);
+  if (k.rowsW) hipFree(k.rowsW);
   k = Cons();
 }
 
@@ -322,8 +323,9 @@ static TriSys path_sys(const Cons& k) {
   return T;
 }
 
-// C(gamma), the tridiagonal path block and the border Schur complement.
-rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma) {
+// C(gamma), the tridiagonal path block and the border Schur complement, of
+// C C^T, or of C W C^T with W = diag(w) per vertex when w is given.
+rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma, const double* w) {
   if (k.k == 0) return RC_OK;
   hipStream_t s = c->stream;
   const int nV = cv.nV, nE = cv.nE;
@@ -335,7 +337,7 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma)
   double* uinv = k.tri_scratch + np;
   int* tinfo = (int*)(k.tri_scratch + 2 * np);
   if (np > 0) {
-    cons_path_coeffs(k.geo, cv.edges, k.path_edge, k.path_prev, np, k.ta, k.td, k.tc, s);
+    cons_path_coeffs(k.geo, cv.edges, k.path_edge, k.path_prev, np, w, k.ta, k.td, k.tc, s);
     tri_prepare(k.ta, k.td, k.tc, k.tri, lo, uinv, k.sp_VW, k.sp_Rt, k.sp_tmp, tinfo, s);
     int info = 0;
     RC_HIP(hipMemcpyAsync(&info, tinfo, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -348,10 +350,16 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma)
   if (k.prow)
     cons_project_pack(k.geo, cv.edges, k.path_edge, np, cv.inc_off, cv.inc, k.edge_path_row, nV, k.prow, k.pvert, s);
   if (nb > 0) {
+    const double* rows2 = k.rows;  // W rows
+    if (w) {
+      if (!k.rowsW) RC_TRY(dalloc(&k.rowsW, (size_t)nb * 3 * nV));
+      cons_scale_rows(k.rows, w, nV, nb, k.rowsW, s);
+      rows2 = k.rowsW;
+    }
     for (int r = 0; r < nb; ++r)
-      vec_dots(k.rows, 3 * nV, k.rows + (size_t)r * 3 * nV, 0, 3 * nV, nb, c->red, k.dots + r * nb, s);
+      vec_dots(k.rows, 3 * nV, rows2 + (size_t)r * 3 * nV, 0, 3 * nV, nb, c->red, k.dots + r * nb, s);
     if (np > 0) {
-      cons_path_apply(k.geo, cv.edges, k.path_edge, np, k.rows, nV, nb, k.Kpb, s);
+      cons_path_apply(k.geo, cv.edges, k.path_edge, np, rows2, nV, nb, k.Kpb, s);
       tri_solve(path_sys(k), k.Kpb, np, k.Z, np, nb, k.sp_g, k.sp_U, s);
       for (int r = 0; r < nb; ++r) vec_dots(k.Kpb, np, k.Z + (size_t)r * np, 0, np, nb, c->red, k.small + r * nb, s);
     }
@@ -380,6 +388,49 @@ static void cons_solve_K(rc_ctx* c, Cons& k) {
   }
 }
 
+// The three-launch projector's data for one level's constraints.
+static ProjData proj_data(const Curve& cv, Cons& k) {
+  ProjData d;
+  d.np = k.np;
+  d.nb = k.nb;
+  d.nV = cv.nV;
+  d.geo = k.geo;
+  d.edges = cv.edges;
+  d.path_edge = k.path_edge;
+  d.rows = k.rows;
+  d.Z = k.Z;
+  d.Sinv = k.Sinv;
+  d.tri = k.tri;
+  d.lo = k.tri_scratch;
+  d.uinv = k.tri_scratch + k.np;
+  d.tc = k.tc;
+  d.V = k.sp_VW;
+  d.W = k.sp_VW + k.np;
+  d.Rt = k.sp_Rt;
+  d.inc_off = cv.inc_off;
+  d.inc = cv.inc;
+  d.edge_path_row = k.edge_path_row;
+  d.prow = k.prow;
+  d.pvert = k.pvert;
+  d.part = k.part;
+  d.g = k.sp_g;
+  d.U = k.sp_U;
+  d.yb = k.yb;
+  return d;
+}
+
+// out = beta prev + scale M in with M = W - W C^T (C W C^T)^-1 C W, W = diag(w):
+// kw holds the factors of C W C^T (cons_prepare with w); nb <= kProjMaxBorder.
+static void cons_project_w(rc_ctx* c, const Curve& cv, Cons& kw, const double* w, const double* in, double* out,
+                           double scale, double beta, const double* prev) {
+  ProjData d = proj_data(cv, kw);
+  d.w = w;
+  d.scale = scale;
+  d.beta = beta;
+  d.prev = prev;
+  cons_project_fused(d, in, out, c->stream);
+}
+
 // out = P in with P = I - C^T (C C^T)^-1 C (in may equal out).
 void cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double* out) {
   hipStream_t s = c->stream;
@@ -389,33 +440,7 @@ void cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double*
     return;
   }
   if (k.nb <= kProjMaxBorder) {
-    ProjData d;
-    d.np = k.np;
-    d.nb = k.nb;
-    d.nV = nV;
-    d.geo = k.geo;
-    d.edges = cv.edges;
-    d.path_edge = k.path_edge;
-    d.rows = k.rows;
-    d.Z = k.Z;
-    d.Sinv = k.Sinv;
-    d.tri = k.tri;
-    d.lo = k.tri_scratch;
-    d.uinv = k.tri_scratch + k.np;
-    d.tc = k.tc;
-    d.V = k.sp_VW;
-    d.W = k.sp_VW + k.np;
-    d.Rt = k.sp_Rt;
-    d.inc_off = cv.inc_off;
-    d.inc = cv.inc;
-    d.edge_path_row = k.edge_path_row;
-    d.prow = k.prow;
-    d.pvert = k.pvert;
-    d.part = k.part;
-    d.g = k.sp_g;
-    d.U = k.sp_U;
-    d.yb = k.yb;
-    cons_project_fused(d, in, out, s);
+    cons_project_fused(proj_data(cv, k), in, out, s);
     return;
   }
   cons_path_apply(k.geo, cv.edges, k.path_edge, k.np, in, nV, 1, k.wp, s);
@@ -569,6 +594,13 @@ static void dense_increment(rc_ctx* c, Dense& d, const double* phi, double* x) {
 // ---------------------------------------------------------------------------
 static const Curve& level_curve(rc_ctx* c, int l) { return l == 0 ? c->curve : c->levels[l]->curve; }
 static Cons& level_cons(rc_ctx* c, int l) { return l == 0 ? c->cons : c->levels[l]->cons; }
+static Cons& level_cons_w(rc_ctx* c, int l) { return l == 0 ? c->cons_w : c->levels[l]->cons_w; }
+
+// w = 1 / d per vertex
+__global__ void k_recip(const double* __restrict__ d, int n, double* __restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = 1.0 / d[i];
+}
 
 rc_status load_geometry(rc_ctx* c, const double* gamma) { return launch_geometry(c->curve, gamma, RC_F32, c->stream); }
 
@@ -577,6 +609,7 @@ void mg_free(rc_ctx* c) {
     if (L) {
       L->curve.release();
       cons_free(L->cons);
+      cons_free(L->cons_w);
       dfree(L->fine_of);
       dfree(L->prolong);
       dfree(L->restr_off);
@@ -585,8 +618,10 @@ void mg_free(rc_ctx* c) {
       L->lowp.release();
     }
   c->levels.clear();
+  cons_free(c->cons_w);
   for (auto& st : c->mg) {
     dfree(st.diag);
+    dfree(st.w);
     dfree(st.x);
     dfree(st.b);
     dfree(st.r);
@@ -679,6 +714,7 @@ static rc_status mg_build(rc_ctx* c) {
     const int n = level_curve(c, l).nV;
     MGLevelState& st = c->mg[l];
     RC_TRY(dalloc(&st.diag, n));
+    RC_TRY(dalloc(&st.w, n));
     double** bufs[] = {&st.x, &st.b, &st.r, &st.d, &st.t, &st.pw};
     for (double** b : bufs) RC_TRY(dalloc(b, 3 * (size_t)n));
     hipLaunchKernelGGL(k_fill_pattern, dim3(cdiv(3 * n, 256)), dim3(256), 0, c->stream, st.pw, 3 * n, 12345u + l);
@@ -719,6 +755,9 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
     if (l > 0) RC_TRY(cons_prepare(c, cv, level_cons(c, l), gl));
   }
   const rc_dtype prec = c->dtype;
+  // the smoothers' weighted projector needs every smoothed level's border in the fused projector
+  c->mg_weighted = c->cons.k > 0;
+  for (int l = 0; l < nl - 1; ++l) c->mg_weighted = c->mg_weighted && level_cons(c, l).nb <= kProjMaxBorder;
   for (int l = 0; l < nl - 1; ++l) {
     const Curve& cv = level_curve(c, l);
     Cons& K = level_cons(c, l);
@@ -729,17 +768,30 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
                                   c->alpha, c->beta, st.diag, s));
     else
       RC_TRY(launch_sobolev(cv, c->alpha, c->beta, prec, st.pw, st.t, st.diag, s));
-    // lambda_max of P D^-1 P A P by power iteration, warm-started from the last call's vector:
-    // at most 12 iterations, stopping once the estimate moves by less than 1 % after at least 3
+    if (c->mg_weighted) {  // factors of C W C^T, W = D^-1
+      Cons& Kw = level_cons_w(c, l);
+      if (Kw.mask != K.mask || !Kw.geo) RC_TRY(cons_alloc(c, cv, Kw, K.mask));
+      RC_HIP(hipMemcpyAsync(Kw.x0, K.x0, sizeof(double) * 3, hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(k_recip, dim3(cdiv(n, 256)), dim3(256), 0, s, st.diag, n, st.w);
+      RC_TRY(cons_prepare(c, cv, Kw, l == 0 ? gamma : c->levels[l]->gamma, st.w));
+    }
+    // lambda_max of the smoother's preconditioned operator (P D^-1 P A P, or M A with the
+    // weighted projector M) by power iteration, warm-started from the last call's vector: at
+    // most 12 iterations, stopping once the estimate moves by less than 1 % after at least 3
     // (warm start) or 8 (first call) of them
     const int min_it = st.lmax > 0.0 ? 3 : 8;
     double nrm = 0.0, prev = 0.0;
     for (int it = 0; it < 12; ++it) {
-      cons_project(c, cv, K, st.pw, st.pw);
-      RC_TRY(apply_level(c, l, st.pw, st.t));
-      cons_project(c, cv, K, st.t, st.t);
-      vec_scale_diag_inv(st.t, st.diag, st.d, n, s);
-      cons_project(c, cv, K, st.d, st.d);
+      if (c->mg_weighted) {
+        RC_TRY(apply_level(c, l, st.pw, st.t));
+        cons_project_w(c, cv, level_cons_w(c, l), st.w, st.t, st.d, 1.0, 0.0, nullptr);
+      } else {
+        cons_project(c, cv, K, st.pw, st.pw);
+        RC_TRY(apply_level(c, l, st.pw, st.t));
+        cons_project(c, cv, K, st.t, st.t);
+        vec_scale_diag_inv(st.t, st.diag, st.d, n, s);
+        cons_project(c, cv, K, st.d, st.d);
+      }
       vec_dot(st.d, st.d, 3 * n, c->red, c->scal, s);
       double h;
       RC_TRY(fetch(c, c->scal, &h, 1));
@@ -771,6 +823,32 @@ static rc_status cheb_smooth(rc_ctx* c, int l, double* x, const double* b, bool 
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
+  if (c->mg_weighted) {
+    // weighted projector M = W - W C^T (C W C^T)^-1 C W (W = D^-1): M annihilates
+    // range(C^T), so the residuals need no projection and each step takes one M
+    Cons& Kw = level_cons_w(c, l);
+    if (x_zero) {
+      hipMemsetAsync(x, 0, sizeof(double) * n3, s);
+      cons_project_w(c, cv, Kw, st.w, b, st.d, 1.0 / theta, 0.0, nullptr);
+      vec_copy(b, st.r, n3, s);
+    } else {
+      RC_TRY(apply_level(c, l, x, st.r));
+      vec_axpby(1.0, b, -1.0, st.r, n3, s);
+      cons_project_w(c, cv, Kw, st.w, st.r, st.d, 1.0 / theta, 0.0, nullptr);
+    }
+    const int deg = c->cheb_deg;
+    for (int k = 0; k < deg; ++k) {
+      vec_axpby(1.0, st.d, 1.0, x, n3, s);
+      if (k == deg - 1) break;
+      RC_TRY(apply_level(c, l, st.d, st.t));
+      vec_axpby(-1.0, st.t, 1.0, st.r, n3, s);
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      // d = c1 d + c2 M r
+      cons_project_w(c, cv, Kw, st.w, st.r, st.d, 2.0 * rn / delta, rn * rho, st.d);
+      rho = rn;
+    }
+    return RC_OK;
+  }
   if (x_zero) {
     vec_copy(b, st.r, n3, s);
     hipMemsetAsync(x, 0, sizeof(double) * n3, s);
