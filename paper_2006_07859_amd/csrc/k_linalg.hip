@@ -213,12 +213,18 @@ __global__ __launch_bounds__(512) void k_chol_solve(const double* __restrict__ L
     }
     __syncthreads();
     for (int idx = tid; idx < nb * mc; idx += 512) B[(size_t)(j0 + idx / mc) * m + c0 + idx % mc] = Bb[idx / mc][idx % mc];
-    for (int idx = tid; idx < (n - j0 - nb) * mc; idx += 512) {
-      const int i = j0 + nb + idx / mc, c = idx % mc;
+    // rows after the block: one thread per row, all of the workgroup's columns
+    for (int i = j0 + nb + tid; i < n; i += 512) {
       const double* Li = L + (size_t)i * n + j0;
-      double v = 0.0;
-      for (int jj = 0; jj < nb; ++jj) v += Li[jj] * Bb[jj][c];
-      B[(size_t)i * m + c0 + c] -= v;
+      double v[kSolveCols];
+#pragma unroll
+      for (int c = 0; c < kSolveCols; ++c) v[c] = 0.0;
+      for (int jj = 0; jj < nb; ++jj) {
+        const double l = Li[jj];
+#pragma unroll
+        for (int c = 0; c < kSolveCols; ++c) v[c] += l * Bb[jj][c];
+      }
+      for (int c = 0; c < mc; ++c) B[(size_t)i * m + c0 + c] -= v[c];
     }
     __syncthreads();
   }
@@ -237,12 +243,17 @@ __global__ __launch_bounds__(512) void k_chol_solve(const double* __restrict__ L
     }
     __syncthreads();
     for (int idx = tid; idx < nb * mc; idx += 512) B[(size_t)(j0 + idx / mc) * m + c0 + idx % mc] = Bb[idx / mc][idx % mc];
-    // rows i < j0: b_i -= sum_jj L[j0 + jj][i] x_{j0 + jj}
-    for (int idx = tid; idx < j0 * mc; idx += 512) {
-      const int i = idx / mc, c = idx % mc;
-      double v = 0.0;
-      for (int jj = 0; jj < nb; ++jj) v += L[(size_t)(j0 + jj) * n + i] * Bb[jj][c];
-      B[(size_t)i * m + c0 + c] -= v;
+    // rows i < j0: b_i -= sum_jj L[j0 + jj][i] x_{j0 + jj}, one thread per row
+    for (int i = tid; i < j0; i += 512) {
+      double v[kSolveCols];
+#pragma unroll
+      for (int c = 0; c < kSolveCols; ++c) v[c] = 0.0;
+      for (int jj = 0; jj < nb; ++jj) {
+        const double l = L[(size_t)(j0 + jj) * n + i];
+#pragma unroll
+        for (int c = 0; c < kSolveCols; ++c) v[c] += l * Bb[jj][c];
+      }
+      for (int c = 0; c < mc; ++c) B[(size_t)i * m + c0 + c] -= v[c];
     }
     __syncthreads();
   }
