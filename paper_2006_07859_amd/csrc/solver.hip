@@ -921,6 +921,24 @@ static rc_status precondition(rc_ctx* c, int kind, const double* r, double* z) {
   return RC_OK;
 }
 
+// x += a p, r -= a q with a = rz / pq read on the device (a = 0 when pq <= 0)
+__global__ void k_pcg_xr(const double* __restrict__ rz, const double* __restrict__ pq, const double* __restrict__ p,
+                         const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = pq[0] > 0.0 ? rz[0] / pq[0] : 0.0;
+  x[i] += a * p[i];
+  r[i] -= a * q[i];
+}
+
+// p = z + (rz_new / rz_old) p
+__global__ void k_pcg_p(const double* __restrict__ rz_new, const double* __restrict__ rz_old,
+                        const double* __restrict__ z, double* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p[i] = z[i] + (rz_new[0] / rz_old[0]) * p[i];
+}
+
 static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve_opts& o, int* iters_out,
                            double* res_out) {
   hipStream_t s = c->stream;
@@ -958,31 +976,31 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
   // true residual
   const bool inexact = (lowp && c->lowp_outer == 1 && o.lowp_outer == 1) || op != RC_F64;
   double window[6];
+  // the recurrence scalars stay on the device (scal[5] = p.q, scal[6] = r.r, r.z alternating in
+  // scal[10], scal[11]); the host reads p.q and r.r once per iteration for the stopping tests
+  double* const sc = c->scal;
+  int par = 0;
   while (it < o.max_iter && !converged) {
     RC_TRY(precondition(c, o.solver, r, z));
     vec_copy(z, p, n3, s);
-    vec_dot(r, z, n3, c->red, c->scal, s);
-    double rz;
-    RC_TRY(fetch(c, c->scal, &rz, 1));
+    vec_dot(r, z, n3, c->red, sc + 10 + par, s);
     int since = 0;
     while (it < o.max_iter) {
       RC_TRY(apply_op(p, q));
       cons_project(c, c->curve, c->cons, q, q);
-      vec_dot(p, q, n3, c->red, c->scal, s);
-      double pq;
-      RC_TRY(fetch(c, c->scal, &pq, 1));
-      if (!(pq > 0)) {
+      vec_dot(p, q, n3, c->red, sc + 5, s);
+      hipLaunchKernelGGL(k_pcg_xr, dim3(cdiv(n3, 256)), dim3(256), 0, s, (const double*)(sc + 10 + par),
+                         (const double*)(sc + 5), (const double*)p, (const double*)q, x, r, n3);
+      vec_dot(r, r, n3, c->red, sc + 6, s);
+      double h[2];
+      RC_TRY(fetch(c, sc + 5, h, 2));
+      const double pq = h[0], rr = h[1];
+      if (!(pq > 0)) {  // x and r were left unchanged
         if (trace_on()) fprintf(stderr, "[rc pcg] it %d breakdown p.q = %.3e\n", it, pq);
         break;
       }
-      const double al = rz / pq;
-      vec_axpby(al, p, 1.0, x, n3, s);
-      vec_axpby(-al, q, 1.0, r, n3, s);
       ++it;
       ++since;
-      vec_dot(r, r, n3, c->red, c->scal, s);
-      double rr;
-      RC_TRY(fetch(c, c->scal, &rr, 1));
       const double res_prev = res;
       res = std::sqrt(rr) / bn;
       if (trace_on()) fprintf(stderr, "[rc pcg] it %d rec-res %.3e\n", it, res);
@@ -1005,8 +1023,9 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
         vec_axpby(-1.0, c->tmp, 1.0, r, n3, s);
         cons_project(c, c->curve, c->cons, r, r);
         vec_dot(r, r, n3, c->red, c->scal, s);
-        RC_TRY(fetch(c, c->scal, &rr, 1));
-        res = std::sqrt(rr) / bn;
+        double rt;
+        RC_TRY(fetch(c, c->scal, &rt, 1));
+        res = std::sqrt(rt) / bn;
         res_sweep = res;
         ++c->last_sweeps;
         if (trace_on()) fprintf(stderr, "[rc pcg] it %d TRUE-res %.3e\n", it, res);
@@ -1014,11 +1033,10 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
         break;
       }
       RC_TRY(precondition(c, o.solver, r, z));
-      vec_dot(r, z, n3, c->red, c->scal, s);
-      double rzn;
-      RC_TRY(fetch(c, c->scal, &rzn, 1));
-      vec_axpby(1.0, z, rzn / rz, p, n3, s);
-      rz = rzn;
+      vec_dot(r, z, n3, c->red, sc + 10 + (par ^ 1), s);
+      hipLaunchKernelGGL(k_pcg_p, dim3(cdiv(n3, 256)), dim3(256), 0, s, (const double*)(sc + 10 + (par ^ 1)),
+                         (const double*)(sc + 10 + par), (const double*)z, p, n3);
+      par ^= 1;
     }
     if (since == 0) break;
   }
