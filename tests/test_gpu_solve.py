@@ -152,12 +152,15 @@ def test_step_multigrid_edge_lengths(lib):
     assert np.abs(phi[3:]).max() < 1e-8 * ell.mean()
 
 
-@pytest.mark.parametrize("n", [3000, 16384, 40000])
+@pytest.mark.parametrize("n", [1025, 1026, 1300, 3000, 16384, 16640, 40000])
 def test_projector_long_loops(lib, n):
-    """Edge-length + barycenter projector on long loops: every chunk length of
-    the tridiagonal solve (registers up to 16 rows per thread, reloads beyond).
-    Against the oracle's dense projector at 3,000 edges; by its defining
-    properties (C P x = 0, P P x = P x, symmetry) at every size."""
+    """Edge-length + barycenter projector on long loops, across the partitions
+    of the tridiagonal path solve: 1,024 path rows (one block, one-launch
+    projector), 1,025 (five blocks, the last of one row), 1,299 and 2,999 (a
+    ragged last block), 16,383 (64 blocks of 256), 16,639 (two rows per thread,
+    a ragged last block) and 39,999 (three rows per thread).  Against the
+    oracle's dense projector up to 3,000 edges; by its defining properties
+    (C P x = 0, P P x = P x, symmetry) at every size."""
     from paper_2006_07859_amd import RC_F64
 
     banner(f"projector with edge-length rows, n={n}")
