@@ -516,7 +516,7 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
     RC_TRY(dalloc(&d.t2, (size_t)std::max(kk, 1)));
     RC_TRY(dalloc(&d.t3, (size_t)n));
     RC_TRY(dalloc(&d.X, (size_t)n * n));
-    RC_TRY(dalloc(&d.info, 1));
+    RC_TRY(dalloc(&d.info, 2));
   }
   RC_TRY(launch_geometry(cv, gamma, RC_F32, s));
   RC_TRY(launch_assemble_dense(cv, c->alpha, c->beta, d.A, s));
@@ -539,38 +539,32 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
   }
   dense_build_H(d.A, d.CtC, nV, d.H, s);
   dense_cholesky(d.H, n, d.info, s);
-  int info = 0;
-  RC_HIP(hipMemcpyAsync(&info, d.info, sizeof(int), hipMemcpyDeviceToHost, s));
-  RC_TRY(sync(c));
-  if (info != 0) {
-    set_error("Cholesky of Abar + C^T C failed: Abar is not definite on null(C)");
-    return RC_ERR_SINGULAR;
-  }
   // X = H^-1 (solve with the identity), then X -= W S^-1 W^T
   hipLaunchKernelGGL(k_identity, dim3(cdiv(n * n, 256)), dim3(256), 0, s, d.X, n);
   dense_chol_solve(d.H, d.X, n, n, s);
   if (kk > 0) {
-    double* Ik;
-    RC_TRY(dalloc(&Ik, (size_t)kk * kk));
-    hipLaunchKernelGGL(k_identity, dim3(cdiv(kk * kk, 256)), dim3(256), 0, s, Ik, kk);
-    dense_gemm(d.Cd, Ik, d.W, n, kk, kk, 0.0, true, s);  // W = C^T
-    dense_chol_solve(d.H, d.W, n, kk, s);                 // W = H^-1 C^T
-    dense_gemm(d.Cd, d.W, d.S, kk, kk, n, 0.0, false, s);
-    std::vector<double> S((size_t)kk * kk);
-    RC_HIP(hipMemcpyAsync(S.data(), d.S, sizeof(double) * kk * kk, hipMemcpyDeviceToHost, s));
-    RC_TRY(sync(c));
-    hipFree(Ik);
-    if (!invert_small(S, kk)) {
-      set_error("constraint Schur complement is singular");
-      return RC_ERR_SINGULAR;
-    }
-    RC_HIP(hipMemcpyAsync(d.Sinv, S.data(), sizeof(double) * kk * kk, hipMemcpyHostToDevice, s));
+    dense_gemm(d.X, d.Cd, d.W, n, kk, n, 0.0, false, s, true);  // W = H^-1 C^T
+    dense_gemm(d.Cd, d.W, d.S, kk, kk, n, 0.0, false, s);       // S = C H^-1 C^T (SPD)
+    dense_cholesky(d.S, kk, d.info + 1, s);
+    hipLaunchKernelGGL(k_identity, dim3(cdiv(kk * kk, 256)), dim3(256), 0, s, d.Sinv, kk);
+    dense_chol_solve(d.S, d.Sinv, kk, kk, s);
     // X += (-W S^-1) W^T, with -W S^-1 staged in CtC (no longer needed)
     dense_gemm(d.W, d.Sinv, d.CtC, n, kk, kk, 0.0, false, s);
     vec_axpby(0.0, d.CtC, -1.0, d.CtC, n * kk, s);
     dense_gemm(d.CtC, d.W, d.X, n, n, kk, 1.0, false, s, true);
   }
-  return sync(c);
+  int info[2] = {0, 0};
+  RC_HIP(hipMemcpyAsync(info, d.info, sizeof(int) * (kk > 0 ? 2 : 1), hipMemcpyDeviceToHost, s));
+  RC_TRY(sync(c));
+  if (info[0] != 0) {
+    set_error("Cholesky of Abar + C^T C failed: Abar is not definite on null(C)");
+    return RC_ERR_SINGULAR;
+  }
+  if (info[1] != 0) {
+    set_error("constraint Schur complement is singular");
+    return RC_ERR_SINGULAR;
+  }
+  return RC_OK;
 }
 
 // x = H^-1 b - W S^-1 W^T b: the saddle solution with right-hand side (b, 0).
