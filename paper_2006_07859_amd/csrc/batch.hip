@@ -400,7 +400,7 @@ constexpr int kGT = 32;
 __global__ __launch_bounds__(256) void k_gj_panel(int k, const int* __restrict__ list,
                                                   const int* __restrict__ chain_voff,
                                                   const long long* __restrict__ blk_off, double* __restrict__ Minv,
-                                                  double* __restrict__ S) {
+                                                  double* __restrict__ S, int* __restrict__ info) {
   __shared__ double D[kGT][kGT + 1];
   __shared__ double f[kGT];
   const int q = list[blockIdx.x];
@@ -421,6 +421,7 @@ __global__ __launch_bounds__(256) void k_gj_panel(int k, const int* __restrict__
   __syncthreads();
   // scalar Gauss-Jordan of the diagonal tile in LDS
   for (int p = 0; p < kGT; ++p) {
+    if (info && tid == 0 && p < kk && !(D[p][p] > 0.0)) atomicMax(info, 1);  // not positive definite
     const double ip = 1.0 / D[p][p];
     __syncthreads();
     if (tid < kGT) {
@@ -495,6 +496,29 @@ __global__ __launch_bounds__(256) void k_gj_update(int k, const int* __restrict_
     for (int s2 = 0; s2 < kGT; ++s2) a += Sa[r][s2] * Bt[s2][c];
     const size_t idx = (size_t)(i0 + r) * m + j0 + c;
     M[idx] = (tj == k) ? -a : M[idx] - a;
+  }
+}
+
+// One block's bookkeeping for the blocked Gauss-Jordan: list {0}, offsets
+// {0, m}, tile prefix {0}, block offset {0}.
+__global__ void k_gj_single_meta(int m, int* __restrict__ meta, long long* __restrict__ off) {
+  meta[0] = 0;  // list
+  meta[1] = 0;  // chain_voff
+  meta[2] = m;
+  meta[3] = 0;  // tile prefix
+  off[0] = 0;
+}
+
+void gj_invert_spd(double* M, int m, int* meta, long long* off, double* col, int* info, hipStream_t s) {
+  hipMemsetAsync(info, 0, sizeof(int), s);
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_gj_single_meta, dim3(1), dim3(1), 0, s, m, meta, off);
+  const int nb = (m + kGT - 1) / kGT;
+  for (int k = 0; k < nb; ++k) {
+    hipLaunchKernelGGL(k_gj_panel, dim3(1), dim3(256), 0, s, k, (const int*)meta, (const int*)(meta + 1),
+                       (const long long*)off, M, col, info);
+    hipLaunchKernelGGL(k_gj_update, dim3(nb * nb), dim3(256), 0, s, k, (const int*)meta, (const int*)(meta + 3), 1,
+                       (const int*)(meta + 1), (const long long*)off, M, (const double*)col);
   }
 }
 
@@ -1449,7 +1473,7 @@ static rc_status b_prepare(rc_ctx* c) {
   for (int k = 0; k < B.gj_steps; ++k) {
     const int off = B.h_gj_step_off[k], nact = B.h_gj_step_off[k + 1] - off;
     hipLaunchKernelGGL(k_gj_panel, dim3(nact), dim3(256), 0, s, k, B.gj_list + off, B.chain_voff, B.blk_off, B.Minv,
-                       B.gj_col);
+                       B.gj_col, (int*)nullptr);
     hipLaunchKernelGGL(k_gj_update, dim3(B.h_gj_tiles[k]), dim3(256), 0, s, k, B.gj_list + off, B.gj_pre + off, nact,
                        B.chain_voff, B.blk_off, B.Minv, (const double*)B.gj_col);
   }

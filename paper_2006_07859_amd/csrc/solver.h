@@ -49,6 +49,9 @@ struct Dense {
   double *A = nullptr, *Cd = nullptr, *CtC = nullptr, *H = nullptr, *W = nullptr, *S = nullptr, *Sinv = nullptr,
          *X = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
   int* info = nullptr;
+  int* gjm = nullptr;        // Gauss-Jordan bookkeeping
+  long long* gjo = nullptr;
+  double* gjc = nullptr;     // Gauss-Jordan column panel scratch
 };
 
 struct Level {

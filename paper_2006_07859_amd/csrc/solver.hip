@@ -486,6 +486,9 @@ void dense_free(Dense& d) {
   dfree(d.W);
   dfree(d.S);
   dfree(d.Sinv);
+  dfree(d.gjm);
+  dfree(d.gjo);
+  dfree(d.gjc);
   dfree(d.t1);
   dfree(d.t2);
   dfree(d.t3);
@@ -506,7 +509,6 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
     d.nV = nV;
     d.k = kk;
     RC_TRY(dalloc(&d.A, (size_t)nV * nV));
-    RC_TRY(dalloc(&d.H, (size_t)n * n));
     RC_TRY(dalloc(&d.CtC, (size_t)n * n));
     RC_TRY(dalloc(&d.Cd, (size_t)std::max(kk, 1) * n));
     RC_TRY(dalloc(&d.W, (size_t)n * std::max(kk, 1)));
@@ -517,6 +519,9 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
     RC_TRY(dalloc(&d.t3, (size_t)n));
     RC_TRY(dalloc(&d.X, (size_t)n * n));
     RC_TRY(dalloc(&d.info, 2));
+    RC_TRY(dalloc(&d.gjm, 4));
+    RC_TRY(dalloc(&d.gjo, 1));
+    RC_TRY(dalloc(&d.gjc, (size_t)32 * std::max(n, kk)));
   }
   RC_TRY(launch_geometry(cv, gamma, RC_F32, s));
   RC_TRY(launch_assemble_dense(cv, c->alpha, c->beta, d.A, s));
@@ -537,17 +542,13 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
     hipLaunchKernelGGL(k_add_const, dim3(cdiv(nV * nV, 256)), dim3(256), 0, s, d.A, nV, tr / ((double)nV * nV));
     RC_HIP(hipMemsetAsync(d.CtC, 0, sizeof(double) * (size_t)n * n, s));
   }
-  dense_build_H(d.A, d.CtC, nV, d.H, s);
-  dense_cholesky(d.H, n, d.info, s);
-  // X = H^-1 (solve with the identity), then X -= W S^-1 W^T
-  hipLaunchKernelGGL(k_identity, dim3(cdiv(n * n, 256)), dim3(256), 0, s, d.X, n);
-  dense_chol_solve(d.H, d.X, n, n, s);
+  // X = H^-1 (H built in X, inverted in place), then X -= W S^-1 W^T
+  dense_build_H(d.A, d.CtC, nV, d.X, s);
+  gj_invert_spd(d.X, n, d.gjm, d.gjo, d.gjc, d.info, s);
   if (kk > 0) {
     dense_gemm(d.X, d.Cd, d.W, n, kk, n, 0.0, false, s, true);  // W = H^-1 C^T
-    dense_gemm(d.Cd, d.W, d.S, kk, kk, n, 0.0, false, s);       // S = C H^-1 C^T (SPD)
-    dense_cholesky(d.S, kk, d.info + 1, s);
-    hipLaunchKernelGGL(k_identity, dim3(cdiv(kk * kk, 256)), dim3(256), 0, s, d.Sinv, kk);
-    dense_chol_solve(d.S, d.Sinv, kk, kk, s);
+    dense_gemm(d.Cd, d.W, d.Sinv, kk, kk, n, 0.0, false, s);    // S = C H^-1 C^T (SPD)
+    gj_invert_spd(d.Sinv, kk, d.gjm, d.gjo, d.gjc, d.info + 1, s);
     // X += (-W S^-1) W^T, with -W S^-1 staged in CtC (no longer needed)
     dense_gemm(d.W, d.Sinv, d.CtC, n, kk, kk, 0.0, false, s);
     vec_axpby(0.0, d.CtC, -1.0, d.CtC, n * kk, s);
