@@ -96,6 +96,8 @@ struct ProjData {
   const double* w = nullptr;
   double scale = 1.0, beta = 0.0;
   const double* prev = nullptr;  // null: no beta term (prev may alias out)
+  double* xacc = nullptr;        // also xacc = out (xset) or xacc += out, per entry
+  bool xset = false;
 };
 void cons_project_fused(const ProjData& d, const double* in, double* out, hipStream_t s);
 void cons_project_pack(const double* geo, const int2* edges, const int* path_edge, int np, const int* inc_off,

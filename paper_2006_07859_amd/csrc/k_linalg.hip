@@ -1108,8 +1108,10 @@ __global__ __launch_bounds__(256) void k_apply_CT_z(const ProjData d, const doub
       for (int cc = 0; cc < 3; ++cc) acc[cc] += ybr[r] * d.rows[((size_t)r * d.nV + v) * 3 + cc];
   const double sw = d.scale * (d.w ? d.w[v] : 1.0);
   for (int cc = 0; cc < 3; ++cc) {
-    const double o = sw * (in[3 * v + cc] - acc[cc]);
-    out[3 * v + cc] = d.prev ? d.beta * d.prev[3 * v + cc] + o : o;
+    const double o0 = sw * (in[3 * v + cc] - acc[cc]);
+    const double o = d.prev ? d.beta * d.prev[3 * v + cc] + o0 : o0;
+    out[3 * v + cc] = o;
+    if (d.xacc) d.xacc[3 * v + cc] = d.xset ? o : d.xacc[3 * v + cc] + o;
   }
 }
 
@@ -1219,15 +1221,12 @@ __global__ __launch_bounds__(kTriThreads) void k_proj_small(const ProjData d, co
       a2 += ybs[r] * rv[2];
     }
   const double sw = d.scale * w_t;
-  const double o0 = sw * (x0 - a0), o1 = sw * (x1 - a1), o2 = sw * (x2 - a2);
-  if (d.prev) {
-    out[3 * t] = d.beta * d.prev[3 * t] + o0;
-    out[3 * t + 1] = d.beta * d.prev[3 * t + 1] + o1;
-    out[3 * t + 2] = d.beta * d.prev[3 * t + 2] + o2;
-  } else {
-    out[3 * t] = o0;
-    out[3 * t + 1] = o1;
-    out[3 * t + 2] = o2;
+  double o[3] = {sw * (x0 - a0), sw * (x1 - a1), sw * (x2 - a2)};
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    if (d.prev) o[cc] += d.beta * d.prev[3 * t + cc];
+    out[3 * t + cc] = o[cc];
+    if (d.xacc) d.xacc[3 * t + cc] = d.xset ? o[cc] : d.xacc[3 * t + cc] + o[cc];
   }
 }
 

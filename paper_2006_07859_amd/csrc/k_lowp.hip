@@ -648,7 +648,8 @@ __global__ __launch_bounds__(256) void k_lowp_finish(const float* __restrict__ p
                                                      const float* __restrict__ band_val, int band,
                                                      const double* __restrict__ sigma_off,
                                                      const double* __restrict__ sqd, const double* __restrict__ X,
-                                                     int n, double* __restrict__ Y) {
+                                                     int n, const double* __restrict__ base, double alpha,
+                                                     double* __restrict__ Y) {
   const int h = threadIdx.x % 32;
   const int v = (blockIdx.x * 256 + threadIdx.x) / 32;
   const bool act = v < n;
@@ -683,7 +684,8 @@ __global__ __launch_bounds__(256) void k_lowp_finish(const float* __restrict__ p
     const double xc = h == 0 ? x0 : h == 1 ? x1 : x2;
     const double cr = X[3 * ((v / 64) * 64) + h];
     const double sh = h == 0 ? s0 : h == 1 ? s1 : s2;
-    Y[3 * v + h] = sv * (sh + sigma_off[v] * sv * (xc - cr));
+    const double y = sv * (sh + sigma_off[v] * sv * (xc - cr));
+    Y[3 * v + h] = base ? base[3 * v + h] + alpha * y : y;  // Y = base + alpha (A X) (Y may alias base)
   }
 }
 
@@ -860,7 +862,8 @@ static void prep(const LowpOp& op, const double* X, hipStream_t s) {
 }
 
 template <typename T>
-static void apply16(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer) {
+static void apply16(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer,
+                    const double* base, double alpha) {
   typedef typename Vec8<T>::type V;
   // FP16 operands need the power-of-two scaling into range; BF16 ones do not
   const double* mx = std::is_same<T, _Float16>::value ? (const double*)op.mx : nullptr;
@@ -873,17 +876,18 @@ static void apply16(const LowpOp& op, const double* X, double* Y, hipStream_t s,
                      op.nkt, op.nsplit, op.per, op.part);
   if (timer) timer->mark(timer->lowp, s);
   hipLaunchKernelGGL(k_lowp_finish, dim3(cdiv(op.n, 8)), dim3(256), 0, s, op.part, op.nsplit, mx, op.band_idx,
-                     op.band_val, op.band, op.sigma, op.sqd, X, op.n, Y);
+                     op.band_val, op.band, op.sigma, op.sqd, X, op.n, base, alpha, Y);
 }
 
-rc_status launch_lowp_apply(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer) {
+rc_status launch_lowp_apply(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer,
+                            const double* base, double alpha) {
   if (!op.ready) {
     set_error("the assembled operator has not been built");
     return RC_ERR_ARG;
   }
   KernelTimer* t = (timer && timer->on) ? timer : nullptr;
-  if (op.fmt == 1) apply16<__bf16>(op, X, Y, s, t);
-  else apply16<_Float16>(op, X, Y, s, t);
+  if (op.fmt == 1) apply16<__bf16>(op, X, Y, s, t, base, alpha);
+  else apply16<_Float16>(op, X, Y, s, t, base, alpha);
   RC_HIP(hipGetLastError());
   return RC_OK;
 }
@@ -902,7 +906,8 @@ rc_status launch_lowp_apply32(const LowpOp& op, const double* X, double* Y, hipS
                      op.nsplit32, op.per32, op.part);
   if (t) t->mark(t->asm32, s);
   hipLaunchKernelGGL(k_lowp_finish, dim3(cdiv(op.n, 8)), dim3(256), 0, s, op.part, op.nsplit32,
-                     (const double*)nullptr, op.band_idx, op.band_val, op.band, op.sigma32, op.sqd, X, op.n, Y);
+                     (const double*)nullptr, op.band_idx, op.band_val, op.band, op.sigma32, op.sqd, X, op.n,
+                     (const double*)nullptr, 1.0, Y);
   RC_HIP(hipGetLastError());
   return RC_OK;
 }

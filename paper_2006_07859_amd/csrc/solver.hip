@@ -421,13 +421,17 @@ static ProjData proj_data(const Curve& cv, Cons& k) {
 
 // out = beta prev + scale M in with M = W - W C^T (C W C^T)^-1 C W, W = diag(w):
 // kw holds the factors of C W C^T (cons_prepare with w); nb <= kProjMaxBorder.
+// With xacc, also xacc = out (xset) or xacc += out.
 static void cons_project_w(rc_ctx* c, const Curve& cv, Cons& kw, const double* w, const double* in, double* out,
-                           double scale, double beta, const double* prev) {
+                           double scale, double beta, const double* prev, double* xacc = nullptr,
+                           bool xset = false) {
   ProjData d = proj_data(cv, kw);
   d.w = w;
   d.scale = scale;
   d.beta = beta;
   d.prev = prev;
+  d.xacc = xacc;
+  d.xset = xset;
   cons_project_fused(d, in, out, c->stream);
 }
 
@@ -820,27 +824,32 @@ static rc_status cheb_smooth(rc_ctx* c, int l, double* x, const double* b, bool 
   double rho = 1.0 / sigma;
   if (c->mg_weighted) {
     // weighted projector M = W - W C^T (C W C^T)^-1 C W (W = D^-1): M annihilates
-    // range(C^T), so the residuals need no projection and each step takes one M
+    // range(C^T), so the residuals need no projection and each step takes one M.
+    // r = base - A X is formed by the product's finish (the 16-bit block) and
+    // x += d by the projector's last launch.
     Cons& Kw = level_cons_w(c, l);
-    if (x_zero) {
-      hipMemsetAsync(x, 0, sizeof(double) * n3, s);
-      cons_project_w(c, cv, Kw, st.w, b, st.d, 1.0 / theta, 0.0, nullptr);
-      vec_copy(b, st.r, n3, s);
-    } else {
-      RC_TRY(apply_level(c, l, x, st.r));
-      vec_axpby(1.0, b, -1.0, st.r, n3, s);
-      cons_project_w(c, cv, Kw, st.w, st.r, st.d, 1.0 / theta, 0.0, nullptr);
-    }
-    const int deg = c->cheb_deg;
-    for (int k = 0; k < deg; ++k) {
-      vec_axpby(1.0, st.d, 1.0, x, n3, s);
-      if (k == deg - 1) break;
-      RC_TRY(apply_level(c, l, st.d, st.t));
+    auto residual = [&](const double* X, const double* base) -> rc_status {  // r = base - A X
+      if (l < c->lowp_levels)
+        return launch_lowp_apply(level_lowp(c, l), X, st.r, s, l == 0 ? &c->timer : nullptr, base, -1.0);
+      RC_TRY(apply_level(c, l, X, st.t));
+      if (base != st.r) vec_copy(base, st.r, n3, s);
       vec_axpby(-1.0, st.t, 1.0, st.r, n3, s);
+      return RC_OK;
+    };
+    if (x_zero) {  // d = M b / theta, x = d
+      cons_project_w(c, cv, Kw, st.w, b, st.d, 1.0 / theta, 0.0, nullptr, x, true);
+      if (c->cheb_deg > 1) RC_TRY(residual(st.d, b));
+    } else {  // r = b - A x, d = M r / theta, x += d
+      RC_TRY(residual(x, b));
+      cons_project_w(c, cv, Kw, st.w, st.r, st.d, 1.0 / theta, 0.0, nullptr, x, false);
+      if (c->cheb_deg > 1) RC_TRY(residual(st.d, st.r));
+    }
+    for (int k = 1; k < c->cheb_deg; ++k) {
       const double rn = 1.0 / (2.0 * sigma - rho);
-      // d = c1 d + c2 M r
-      cons_project_w(c, cv, Kw, st.w, st.r, st.d, 2.0 * rn / delta, rn * rho, st.d);
+      // d = c1 d + c2 M r, x += d
+      cons_project_w(c, cv, Kw, st.w, st.r, st.d, 2.0 * rn / delta, rn * rho, st.d, x, false);
       rho = rn;
+      if (k + 1 < c->cheb_deg) RC_TRY(residual(st.d, st.r));
     }
     return RC_OK;
   }
