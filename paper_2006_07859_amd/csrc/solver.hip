@@ -435,22 +435,27 @@ static void cons_project_w(rc_ctx* c, const Curve& cv, Cons& kw, const double* w
   cons_project_fused(d, in, out, c->stream);
 }
 
-// out = P in with P = I - C^T (C C^T)^-1 C (in may equal out).
-void cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double* out) {
+// out = P in with P = I - C^T (C C^T)^-1 C (in may equal out); with xacc, also
+// xacc += out.
+void cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double* out, double* xacc) {
   hipStream_t s = c->stream;
   const int nV = cv.nV;
   if (k.k == 0) {
     if (in != out) vec_copy(in, out, 3 * nV, s);
+    if (xacc) vec_axpby(1.0, out, 1.0, xacc, 3 * nV, s);
     return;
   }
   if (k.nb <= kProjMaxBorder) {
-    cons_project_fused(proj_data(cv, k), in, out, s);
+    ProjData d = proj_data(cv, k);
+    d.xacc = xacc;
+    cons_project_fused(d, in, out, s);
     return;
   }
   cons_path_apply(k.geo, cv.edges, k.path_edge, k.np, in, nV, 1, k.wp, s);
   if (k.nb > 0) vec_dots(k.rows, 3 * nV, in, 0, 3 * nV, k.nb, c->red, k.wb, s);
   cons_solve_K(c, k);
   cons_apply_CT(k.geo, cv.inc_off, cv.inc, k.edge_path_row, k.yp, k.rows, k.yb, k.nb, nV, in, out, s);
+  if (xacc) vec_axpby(1.0, out, 1.0, xacc, 3 * nV, s);
 }
 
 // z = C^T (C C^T)^-1 b for an external-order b (finest level).
@@ -892,8 +897,12 @@ static rc_status vcycle(rc_ctx* c, int l, const double* b, double* x) {
   MGLevelState& st = c->mg[l];
   const int n3 = 3 * cv.nV;
   RC_TRY(cheb_smooth(c, l, x, b, true));
-  RC_TRY(apply_level(c, l, x, st.t));
-  vec_axpby(1.0, b, -1.0, st.t, n3, s);  // t = b - A x
+  if (l < c->lowp_levels) {  // t = b - A x
+    RC_TRY(launch_lowp_apply(level_lowp(c, l), x, st.t, s, l == 0 ? &c->timer : nullptr, b, -1.0));
+  } else {
+    RC_TRY(apply_level(c, l, x, st.t));
+    vec_axpby(1.0, b, -1.0, st.t, n3, s);
+  }
   cons_project(c, cv, K, st.t, st.t);
   Level& C = *c->levels[l + 1];
   MGLevelState& sc = c->mg[l + 1];
@@ -902,8 +911,7 @@ static rc_status vcycle(rc_ctx* c, int l, const double* b, double* x) {
   cons_project(c, C.curve, C.cons, sc.b, sc.b);
   RC_TRY(vcycle(c, l + 1, sc.b, sc.x));
   hipLaunchKernelGGL(k_prolong, dim3(cdiv(cv.nV, 256)), dim3(256), 0, s, C.prolong, cv.nV, sc.x, st.t);
-  cons_project(c, cv, K, st.t, st.t);
-  vec_axpby(1.0, st.t, 1.0, x, n3, s);
+  cons_project(c, cv, K, st.t, st.t, x);  // x += P J x_c
   RC_TRY(cheb_smooth(c, l, x, b, false));
   return RC_OK;
 }
@@ -917,8 +925,7 @@ static rc_status precondition(rc_ctx* c, int kind, const double* r, double* z) {
   if (kind == RC_SOLVE_PCG_MULTILEVEL || kind == RC_SOLVE_PCG_LEARNED) return learn_apply(c, r, z);
   if (kind == RC_SOLVE_PCG_MG) {
     MGLevelState& st = c->mg[0];
-    vec_copy(r, st.b, 3 * c->nV, c->stream);
-    return vcycle(c, 0, st.b, z);
+    return vcycle(c, 0, r, z);  // the V-cycle only reads its right-hand side
   }
   vec_scale_diag_inv(r, c->diag, z, c->nV, c->stream);
   cons_project(c, c->curve, c->cons, z, z);
