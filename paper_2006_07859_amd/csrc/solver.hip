@@ -908,7 +908,10 @@ static rc_status vcycle(rc_ctx* c, int l, const double* b, double* x) {
   MGLevelState& sc = c->mg[l + 1];
   hipLaunchKernelGGL(k_restrict, dim3(cdiv(C.curve.nV, 256)), dim3(256), 0, s, C.restr_off, C.restr_idx, C.prolong,
                      C.curve.nV, st.t, sc.b);
-  cons_project(c, C.curve, C.cons, sc.b, sc.b);
+  // With the weighted smoother every use of the coarse right-hand side (M b, M (b - A x), the
+  // Euclidean P of the coarse residual, and the coarsest level's saddle solve X b) annihilates
+  // range(C^T) of the coarse level, so projecting it first would not change the V-cycle.
+  if (!c->mg_weighted) cons_project(c, C.curve, C.cons, sc.b, sc.b);
   RC_TRY(vcycle(c, l + 1, sc.b, sc.x));
   hipLaunchKernelGGL(k_prolong, dim3(cdiv(cv.nV, 256)), dim3(256), 0, s, C.prolong, cv.nV, sc.x, st.t);
   cons_project(c, cv, K, st.t, st.t, x);  // x += P J x_c
