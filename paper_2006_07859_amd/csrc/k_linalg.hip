@@ -84,185 +84,8 @@ void vec_dots(const double* X, int ldx, const double* Y, int ldy, int n, int m, 
 int dot_scratch_size(int m) { return kRedBlocks * m; }
 
 // ---------------------------------------------------------------------------
-// blocked dense Cholesky (lower, row-major, in place), block size 32
+// dense products (the coarsest level's saddle operator)
 // ---------------------------------------------------------------------------
-constexpr int kNB = 32;
-
-__global__ void k_potrf_diag(double* __restrict__ A, int n, int k0, int* __restrict__ info) {
-  __shared__ double L[kNB][kNB + 1];
-  const int nb = min(kNB, n - k0);
-  const int tid = threadIdx.x;  // 256 threads
-  for (int idx = tid; idx < nb * nb; idx += 256) {
-    int i = idx / nb, j = idx % nb;
-    L[i][j] = A[(size_t)(k0 + i) * n + k0 + j];
-  }
-  __syncthreads();
-  for (int k = 0; k < nb; ++k) {
-    if (tid == 0) {
-      double d = L[k][k];
-      if (!(d > 0.0)) {
-        if (info[0] == 0) info[0] = k0 + k + 1;
-        d = 1.0;
-      }
-      L[k][k] = sqrt(d);
-    }
-    __syncthreads();
-    const double piv = L[k][k];
-    for (int i = k + 1 + tid; i < nb; i += 256) L[i][k] /= piv;
-    __syncthreads();
-    for (int idx = tid; idx < (nb - k - 1) * (nb - k - 1); idx += 256) {
-      int i = k + 1 + idx / (nb - k - 1), j = k + 1 + idx % (nb - k - 1);
-      if (j <= i) L[i][j] -= L[i][k] * L[j][k];
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < nb * nb; idx += 256) {
-    int i = idx / nb, j = idx % nb;
-    A[(size_t)(k0 + i) * n + k0 + j] = (j <= i) ? L[i][j] : 0.0;
-  }
-}
-
-// Rows below the diagonal block: A[i, k0:k0+nb] <- A[i, k0:k0+nb] L_kk^-T.
-// One thread per row; 64 rows per block.
-__global__ void k_trsm_panel(double* __restrict__ A, int n, int k0) {
-  __shared__ double L[kNB][kNB + 1];
-  const int nb = min(kNB, n - k0);
-  for (int idx = threadIdx.x; idx < nb * nb; idx += blockDim.x) {
-    int i = idx / nb, j = idx % nb;
-    L[i][j] = A[(size_t)(k0 + i) * n + k0 + j];
-  }
-  __syncthreads();
-  const int i = k0 + nb + blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double x[kNB];
-  for (int j = 0; j < nb; ++j) x[j] = A[(size_t)i * n + k0 + j];
-  for (int j = 0; j < nb; ++j) {
-    double v = x[j];
-    for (int p = 0; p < j; ++p) v -= x[p] * L[j][p];
-    x[j] = v / L[j][j];
-  }
-  for (int j = 0; j < nb; ++j) A[(size_t)i * n + k0 + j] = x[j];
-}
-
-// Trailing update A[i,j] -= sum_p A[i,k0+p] A[j,k0+p] for i >= j >= k1 = k0+nb.
-// 32x32 output tiles, 256 threads, each 4 outputs.
-__global__ void k_syrk_update(double* __restrict__ A, int n, int k0) {
-  const int nb = min(kNB, n - k0);
-  const int k1 = k0 + nb;
-  const int ti = blockIdx.y, tj = blockIdx.x;
-  if (tj > ti) return;
-  const int i0 = k1 + ti * 32, j0 = k1 + tj * 32;
-  __shared__ double Pi[32][kNB + 1], Pj[32][kNB + 1];
-  for (int idx = threadIdx.x; idx < 32 * nb; idx += 256) {
-    int r = idx / nb, p = idx % nb;
-    Pi[r][p] = (i0 + r < n) ? A[(size_t)(i0 + r) * n + k0 + p] : 0.0;
-    Pj[r][p] = (j0 + r < n) ? A[(size_t)(j0 + r) * n + k0 + p] : 0.0;
-  }
-  __syncthreads();
-  for (int q = 0; q < 4; ++q) {
-    int idx = threadIdx.x + 256 * q;
-    int r = idx / 32, cc = idx % 32;
-    int i = i0 + r, j = j0 + cc;
-    if (i >= n || j >= n || j > i) continue;
-    double s = 0.0;
-    for (int p = 0; p < nb; ++p) s += Pi[r][p] * Pj[cc][p];
-    A[(size_t)i * n + j] -= s;
-  }
-}
-
-void dense_cholesky(double* A, int n, int* info, hipStream_t s) {
-  hipMemsetAsync(info, 0, sizeof(int), s);
-  for (int k0 = 0; k0 < n; k0 += kNB) {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, n, k0, info);
-    const int rest = n - k0 - kNB;
-    if (rest <= 0) break;
-    hipLaunchKernelGGL(k_trsm_panel, dim3(cdiv(rest, 64)), dim3(64), 0, s, A, n, k0);
-    const int nt = cdiv(rest, 32);
-    hipLaunchKernelGGL(k_syrk_update, dim3(nt, nt), dim3(256), 0, s, A, n, k0);
-  }
-}
-
-// L L^T X = B, B is n x m row-major; each workgroup owns up to kSolveCols
-// right-hand-side columns.
-constexpr int kSolveCols = 4;
-constexpr int kSolveRows = 32;  // row block of the blocked substitution
-
-// Blocked substitution: for each block of 32 rows, the block's triangular
-// system is solved in LDS (one thread per right-hand-side column, no barriers
-// inside), then the rows after it (forward) or before it (backward) take a
-// rank-32 update.  512 threads per workgroup, kSolveCols columns.
-__global__ __launch_bounds__(512) void k_chol_solve(const double* __restrict__ L, double* __restrict__ B, int n,
-                                                     int m) {
-  __shared__ double Ld[kSolveRows][kSolveRows + 1];
-  __shared__ double Bb[kSolveRows][kSolveCols + 1];
-  const int tid = threadIdx.x;
-  const int c0 = blockIdx.x * kSolveCols;
-  const int mc = min(kSolveCols, m - c0);
-  // forward: L y = b
-  for (int j0 = 0; j0 < n; j0 += kSolveRows) {
-    const int nb = min(kSolveRows, n - j0);
-    for (int idx = tid; idx < nb * nb; idx += 512) Ld[idx / nb][idx % nb] = L[(size_t)(j0 + idx / nb) * n + j0 + idx % nb];
-    for (int idx = tid; idx < nb * mc; idx += 512) Bb[idx / mc][idx % mc] = B[(size_t)(j0 + idx / mc) * m + c0 + idx % mc];
-    __syncthreads();
-    if (tid < mc) {
-      for (int i = 0; i < nb; ++i) {
-        double v = Bb[i][tid];
-        for (int jj = 0; jj < i; ++jj) v -= Ld[i][jj] * Bb[jj][tid];
-        Bb[i][tid] = v / Ld[i][i];
-      }
-    }
-    __syncthreads();
-    for (int idx = tid; idx < nb * mc; idx += 512) B[(size_t)(j0 + idx / mc) * m + c0 + idx % mc] = Bb[idx / mc][idx % mc];
-    // rows after the block: one thread per row, all of the workgroup's columns
-    for (int i = j0 + nb + tid; i < n; i += 512) {
-      const double* Li = L + (size_t)i * n + j0;
-      double v[kSolveCols];
-#pragma unroll
-      for (int c = 0; c < kSolveCols; ++c) v[c] = 0.0;
-      for (int jj = 0; jj < nb; ++jj) {
-        const double l = Li[jj];
-#pragma unroll
-        for (int c = 0; c < kSolveCols; ++c) v[c] += l * Bb[jj][c];
-      }
-      for (int c = 0; c < mc; ++c) B[(size_t)i * m + c0 + c] -= v[c];
-    }
-    __syncthreads();
-  }
-  // backward: L^T x = y, blocks from the last
-  for (int j0 = ((n - 1) / kSolveRows) * kSolveRows; j0 >= 0; j0 -= kSolveRows) {
-    const int nb = min(kSolveRows, n - j0);
-    for (int idx = tid; idx < nb * nb; idx += 512) Ld[idx / nb][idx % nb] = L[(size_t)(j0 + idx / nb) * n + j0 + idx % nb];
-    for (int idx = tid; idx < nb * mc; idx += 512) Bb[idx / mc][idx % mc] = B[(size_t)(j0 + idx / mc) * m + c0 + idx % mc];
-    __syncthreads();
-    if (tid < mc) {
-      for (int i = nb - 1; i >= 0; --i) {
-        double v = Bb[i][tid];
-        for (int jj = i + 1; jj < nb; ++jj) v -= Ld[jj][i] * Bb[jj][tid];
-        Bb[i][tid] = v / Ld[i][i];
-      }
-    }
-    __syncthreads();
-    for (int idx = tid; idx < nb * mc; idx += 512) B[(size_t)(j0 + idx / mc) * m + c0 + idx % mc] = Bb[idx / mc][idx % mc];
-    // rows i < j0: b_i -= sum_jj L[j0 + jj][i] x_{j0 + jj}, one thread per row
-    for (int i = tid; i < j0; i += 512) {
-      double v[kSolveCols];
-#pragma unroll
-      for (int c = 0; c < kSolveCols; ++c) v[c] = 0.0;
-      for (int jj = 0; jj < nb; ++jj) {
-        const double l = L[(size_t)(j0 + jj) * n + i];
-#pragma unroll
-        for (int c = 0; c < kSolveCols; ++c) v[c] += l * Bb[jj][c];
-      }
-      for (int c = 0; c < mc; ++c) B[(size_t)i * m + c0 + c] -= v[c];
-    }
-    __syncthreads();
-  }
-}
-
-void dense_chol_solve(const double* L, double* B, int n, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_solve, dim3(cdiv(m, kSolveCols)), dim3(512), 0, s, L, B, n, m);
-}
-
 // C[m x n] = op(A) op(B) + beta C, row-major; op(A) is m x k (A stored k x m
 // when transA), op(B) is k x n (B stored n x k when transB).
 __global__ void k_gemm(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C, int m,

@@ -272,15 +272,11 @@ void vec_copy(const double* x, double* y, int n, hipStream_t s);
 void vec_scale_diag_inv(const double* r, const double* d, double* z, int nV, hipStream_t s); // z = r / d (3 comps)
 // result[0] = x . y (deterministic two-pass reduction), on device
 void vec_dot(const double* x, const double* y, int n, double* scratch, double* result, hipStream_t s);
-// Dense Cholesky factorisation in place (lower), n x n row-major; info[0] = 0 on success.
-void dense_cholesky(double* A, int n, int* info, hipStream_t s);
 // In-place inverse of an m x m symmetric positive definite matrix (row major)
 // by blocked Gauss-Jordan with 32 x 32 tiles (batch.hip); meta: device int[4],
 // off: device long long[1], col: device double[32 m] scratch; info: device int,
 // nonzero when a pivot is not positive.
 void gj_invert_spd(double* M, int m, int* meta, long long* off, double* col, int* info, hipStream_t s);
-// Solve L L^T X = B in place, B is n x m row-major.
-void dense_chol_solve(const double* L, double* B, int n, int m, hipStream_t s);
 // C = A B (+ beta C): small dense FP64 GEMM, row-major, all device.
 void dense_gemm(const double* A, const double* B, double* C, int m, int n, int k, double beta,
                 bool transA, hipStream_t s, bool transB = false);

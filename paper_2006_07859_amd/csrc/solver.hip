@@ -164,10 +164,6 @@ __global__ void k_add_const(double* __restrict__ A, int n, double rho) {
   if (i < n * n) A[i] += rho;
 }
 
-__global__ void k_identity(double* __restrict__ A, int n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n * n) A[i] = (i / n == i % n) ? 1.0 : 0.0;
-}
 
 __global__ void k_negate(const double* __restrict__ in, double* __restrict__ out, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
