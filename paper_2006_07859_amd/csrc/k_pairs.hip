@@ -57,6 +57,45 @@ __device__ __forceinline__ bool chain_near(int4 ci, int4 cj) {
   return (cj.x == ci.x) & (dd <= kBand);
 }
 
+// Range (min chain, max chain, min position, max position) of the chain
+// coordinates held by the valid threads of a workgroup of kTile threads: each
+// wave reduces with cross-lane exchanges and writes its slot of red; after a
+// barrier, range_of(red) combines the slots.
+__device__ __forceinline__ void wave_range(int4 c, bool valid, int4* red) {
+  int cmin = valid ? c.x : INT_MAX, cmax = valid ? c.x : INT_MIN;
+  int pmin = valid ? c.y : INT_MAX, pmax = valid ? c.y : INT_MIN;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    cmin = min(cmin, __shfl_xor(cmin, o));
+    cmax = max(cmax, __shfl_xor(cmax, o));
+    pmin = min(pmin, __shfl_xor(pmin, o));
+    pmax = max(pmax, __shfl_xor(pmax, o));
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_int4(cmin, cmax, pmin, pmax);
+}
+
+__device__ __forceinline__ int4 range_of(const int4* red) {
+  int4 r = red[0];
+#pragma unroll
+  for (int w = 1; w < kTile / 64; ++w) {
+    const int4 v = red[w];
+    r = make_int4(min(r.x, v.x), max(r.y, v.y), min(r.z, v.z), max(r.w, v.w));
+  }
+  return r;
+}
+
+// True when no target of range tr is chain-near any source of range sr: the
+// chain ranges are disjoint, or both tiles lie on one chain (length m, a loop
+// when loop != 0) with position intervals more than kBand apart, also around
+// the loop.  Conservative: false whenever the ranges cannot decide.
+__device__ __forceinline__ bool tiles_far(int4 tr, int4 sr, int m, int loop) {
+  if (tr.y < sr.x || sr.y < tr.x) return true;
+  if (tr.x != tr.y || sr.x != sr.y) return false;
+  const int gap = max(sr.z - tr.w, tr.z - sr.w);
+  if (gap <= kBand) return false;
+  return !loop || m - (max(tr.w, sr.w) - min(tr.z, sr.z)) > kBand;
+}
+
 // BAND: the graph is a union of chains and the kernel runs in FP32; pairs
 // that are chain-near (which include every pair sharing a vertex) are left
 // to the FP64 near-band kernel.  Otherwise only pairs sharing a vertex are
@@ -75,6 +114,8 @@ __device__ __forceinline__ void tpe_tile(const V4<R>* __restrict__ GA, const V4<
   __shared__ V4<R> sA[kTile], sB[kTile], sT[kTile];
   __shared__ int2 sE[kTile];
   __shared__ int4 sC[BAND ? kTile : 1];
+  __shared__ int4 sRed[2][kTile / 64];  // chain ranges: [0] targets, [1] the staged sources
+  __shared__ int2 sChain;               // (length, is loop) of the first target's chain
   const int tid = threadIdx.x;
   const int I = I0 + tid;
   const bool act = tid < tcount;
@@ -82,7 +123,11 @@ __device__ __forceinline__ void tpe_tile(const V4<R>* __restrict__ GA, const V4<
   const V4<R> a = GA[Ic], b = GB[Ic], t = GT[Ic];
   const int2 ei = act ? edges[Ic] : make_int2(-1, -2);
   int4 ci = make_int4(-1, 0, 0, 0);
-  if constexpr (BAND) ci = act ? cinfo[Ic] : make_int4(-1, 0, 0, 0);
+  if constexpr (BAND) {
+    ci = act ? cinfo[Ic] : make_int4(-1, 0, 0, 0);
+    wave_range(ci, act, sRed[0]);
+    if (tid == 0) sChain = make_int2(ci.z, ci.w);  // thread 0 always holds a target
+  }
   constexpr int NS = GRAD ? kTpeSlots : 1;
   double acc[NS];
 #pragma unroll
@@ -91,53 +136,64 @@ __device__ __forceinline__ void tpe_tile(const V4<R>* __restrict__ GA, const V4<
   for (int t0 = s0; t0 < s1; t0 += kTile) {
     __syncthreads();
     if (t0 + tid < s1) {
-      sA[tid] = GA[t0 + tid];
-      sB[tid] = GB[t0 + tid];
+      const V4<R> qa = GA[t0 + tid];
+      V4<R> qb = GB[t0 + tid];
+      qb.w = R(0.25) * qa.w;
+      sA[tid] = qa;
+      sB[tid] = qb;
       sT[tid] = GT[t0 + tid];
       sE[tid] = edges[t0 + tid];
-      if constexpr (BAND) sC[tid] = cinfo[t0 + tid];
+    }
+    if constexpr (BAND) {
+      const bool staged = t0 + tid < s1;
+      const int4 cj = staged ? cinfo[t0 + tid] : make_int4(-1, 0, 0, 0);
+      if (staged) sC[tid] = cj;
+      wave_range(cj, staged, sRed[1]);
     }
     __syncthreads();
     const int cnt = min(kTile, s1 - t0);
+    // Pairs are tested (and skipped) one by one only where the tile ranges
+    // cannot rule out a chain-near or vertex-sharing pair.
+    bool test = true;
+    if constexpr (BAND) test = !tiles_far(range_of(sRed[0]), range_of(sRed[1]), sChain.x, sChain.y);
     for (int u0 = 0; u0 < cnt; u0 += kSub) {
       const int u1 = min(cnt, u0 + kSub);
       R E = 0, S = 0, G1x = 0, G1y = 0, G1z = 0, G2x = 0, G2y = 0, G2z = 0;
-      R Gt1 = 0, Gt2 = 0, Hx = 0, Hy = 0, Hz = 0, Ht = 0;
-      for (int u = u0; u < u1; ++u) {
-        const V4<R> qa = sA[u], qb = sB[u], qt = sT[u];
-        bool s11, s12, s21, s22, skip;
-        if constexpr (BAND) {
-          skip = chain_near(ci, sC[u]);
-          s11 = s12 = s21 = s22 = skip;
-        } else {
-          const int2 ej = sE[u];
-          s11 = ei.x == ej.x;
-          s12 = ei.x == ej.y;
-          s21 = ei.y == ej.x;
-          s22 = ei.y == ej.y;
-          skip = s11 | s12 | s21 | s22;
+      R Gt1 = 0, Gt2 = 0, Hx = 0, Hy = 0, Hz = 0;
+      auto sweep = [&](auto tested) {
+        for (int u = u0; u < u1; ++u) {
+          const V4<R> qa = sA[u], qb = sB[u], qt = sT[u];
+          if constexpr (decltype(tested)::value) {
+            bool skip;
+            if constexpr (BAND) {
+              skip = chain_near(ci, sC[u]);
+            } else {
+              const int2 ej = sE[u];
+              skip = (ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y);
+            }
+            const R w = skip ? R(0) : qb.w;  // l_J / 4, staged in the free slot
+            tpe_edge_pair<R, EC, GRAD, true>(a.x, a.y, a.z, b.x, b.y, b.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z,
+                                             qb.x, qb.y, qb.z, qt.x, qt.y, qt.z, qa.w, w, skip ? R(1) : R(0),
+                                             half_alpha, half_beta, beta, E, S, G1x, G1y, G1z, Gt1, G2x, G2y,
+                                             G2z, Gt2, Hx, Hy, Hz);
+          } else {
+            tpe_edge_pair<R, EC, GRAD, false>(a.x, a.y, a.z, b.x, b.y, b.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z,
+                                              qb.x, qb.y, qb.z, qt.x, qt.y, qt.z, qa.w, qb.w, R(0), half_alpha,
+                                              half_beta, beta, E, S, G1x, G1y, G1z, Gt1, G2x, G2y, G2z, Gt2, Hx,
+                                              Hy, Hz);
+          }
         }
-        const R w = skip ? R(0) : R(0.25) * qa.w;
-        tpe_vertex_pair<R, EC, GRAD>(a.x, a.y, a.z, t.x, t.y, t.z, qa.x, qa.y, qa.z, qt.x, qt.y, qt.z,
-                                     s11, w, half_alpha, half_beta, beta, E, S, G1x, G1y, G1z, Gt1,
-                                     Hx, Hy, Hz, Ht);
-        tpe_vertex_pair<R, EC, GRAD>(a.x, a.y, a.z, t.x, t.y, t.z, qb.x, qb.y, qb.z, qt.x, qt.y, qt.z,
-                                     s12, w, half_alpha, half_beta, beta, E, S, G1x, G1y, G1z, Gt1,
-                                     Hx, Hy, Hz, Ht);
-        tpe_vertex_pair<R, EC, GRAD>(b.x, b.y, b.z, t.x, t.y, t.z, qa.x, qa.y, qa.z, qt.x, qt.y, qt.z,
-                                     s21, w, half_alpha, half_beta, beta, E, S, G2x, G2y, G2z, Gt2,
-                                     Hx, Hy, Hz, Ht);
-        tpe_vertex_pair<R, EC, GRAD>(b.x, b.y, b.z, t.x, t.y, t.z, qb.x, qb.y, qb.z, qt.x, qt.y, qt.z,
-                                     s22, w, half_alpha, half_beta, beta, E, S, G2x, G2y, G2z, Gt2,
-                                     Hx, Hy, Hz, Ht);
-      }
+      };
+      if (test) sweep(std::true_type{});
+      else sweep(std::false_type{});
       acc[0] += (double)E;
       if constexpr (GRAD) {
         acc[1] += (double)S;
         acc[2] += (double)G1x; acc[3] += (double)G1y; acc[4] += (double)G1z;
         acc[5] += (double)G2x; acc[6] += (double)G2y; acc[7] += (double)G2z;
         acc[8] += (double)Gt1; acc[9] += (double)Gt2;
-        acc[10] += (double)Hx; acc[11] += (double)Hy; acc[12] += (double)Hz; acc[13] += (double)Ht;
+        acc[10] += (double)Hx; acc[11] += (double)Hy; acc[12] += (double)Hz;
+        acc[13] += (double)(t.x * Hx + t.y * Hy + t.z * Hz);  // T.H: H holds multiples of T
       }
     }
   }
