@@ -38,7 +38,10 @@ sys.path.insert(0, ROOT)
 # evaluating the four vertex pairs independently would take 344.
 FLOPS_PER_PAIR_TPE = 280   # energy + differential, algorithmic
 FLOPS_PER_PAIR_TPE_EXEC = 214  # energy + differential, executed by the (2, 4.5) FP32 kernel
-FLOPS_PER_PAIR_SOB = 198   # operator A = B + B0 applied to 3 right-hand sides
+# Operator A = B + B0 applied to 3 right-hand sides: about 100 flops per pair for
+# the gather form; the FP32 kernel executes 144 and 8 transcendentals per pair, the
+# FP64 one 196 with its powers from an FP32 estimate and Newton steps.
+FLOPS_PER_PAIR_SOB = 100   # operator, algorithmic
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed); the non-packed issue limit is half
 PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E

@@ -413,18 +413,22 @@ __device__ __forceinline__ void sob_tile(const V4<R>* __restrict__ GA, const V4<
                                          double* __restrict__ part) {
   __shared__ V4<R> sA[kTile], sB[kTile], sT[kTile], sS[kTile], sU[kTile];
   __shared__ int2 sE[kTile];
+  __shared__ int4 sRed[2][kTile / 64];  // vertex ranges: [0] targets, [1] the staged sources
   const int tid = threadIdx.x;
   const int I = I0 + tid;
   const bool act = tid < tcount;
   const int Ic = act ? I : I0;
   const V4<R> a = GA[Ic], b = GB[Ic], t = GT[Ic];
   const int2 ei = act ? edges[Ic] : make_int2(-1, -2);
+  wave_range(make_int4(min(ei.x, ei.y), max(ei.x, ei.y), 0, 0), act, sRed[0]);
   double acc[kSobSlots];
 #pragma unroll
   for (int k = 0; k < kSobSlots; ++k) acc[k] = 0.0;
   for (int t0 = s0; t0 < s1; t0 += kTile) {
     __syncthreads();
-    if (t0 + tid < s1) {
+    const bool staged = t0 + tid < s1;
+    int2 ej = make_int2(-1, -2);
+    if (staged) {
       const int j = t0 + tid;
       V4<R> ga = GA[j], gs = RS[j];
       const R il = R(1) / ga.w;
@@ -433,49 +437,48 @@ __device__ __forceinline__ void sob_tile(const V4<R>* __restrict__ GA, const V4<
       sT[tid] = GT[j];
       sS[tid] = V4<R>{gs.x * il, gs.y * il, gs.z * il, R(0)};
       sU[tid] = RU[j];
-      sE[tid] = edges[j];
+      ej = edges[j];
+      sE[tid] = ej;
     }
+    wave_range(make_int4(min(ej.x, ej.y), max(ej.x, ej.y), 0, 0), staged, sRed[1]);
     __syncthreads();
     const int cnt = min(kTile, s1 - t0);
+    // Pairs are tested for a shared vertex one by one only where the vertex
+    // ranges of the two tiles overlap.
+    const int4 tr = range_of(sRed[0]), sr = range_of(sRed[1]);
+    const bool test = !(tr.w < sr.x || sr.w < tr.x);
     for (int u0 = 0; u0 < cnt; u0 += kSub) {
       const int u1 = min(cnt, u0 + kSub);
       R Wq = 0, Qx = 0, Qy = 0, Qz = 0, P0 = 0, Px = 0, Py = 0, Pz = 0;
-      for (int u = u0; u < u1; ++u) {
-        const V4<R> qa = sA[u], qb = sB[u], qt = sT[u];
-        const int2 ej = sE[u];
-        const bool s11 = ei.x == ej.x, s12 = ei.x == ej.y, s21 = ei.y == ej.x, s22 = ei.y == ej.y;
-        const R w = (s11 | s12 | s21 | s22) ? R(0) : qa.w;
-        R rho = 0, rho0 = 0;
-#define RC_SOB_VP(PX, QX, SAME)                                                    \
-  {                                                                                \
-    R dx = PX.x - QX.x, dy = PX.y - QX.y, dz = PX.z - QX.z;                       \
-    R r2 = dx * dx + dy * dy + dz * dz;                                            \
-    r2 = (SAME) ? R(1) : r2;                                                       \
-    R rs = f_rsq<R>(r2);                                                           \
-    R ri = rs * rs;                                                                \
-    R p = pow_sigma<EC, R>(r2, rs, ri, half_expo);                                 \
-    R cI = cross_norm2<R>(t.x, t.y, t.z, dx, dy, dz);                              \
-    R cJ = cross_norm2<R>(qt.x, qt.y, qt.z, dx, dy, dz);                           \
-    rho += p;                                                                      \
-    rho0 += p * (cI + cJ) * ri * ri;                                               \
-  }
-        RC_SOB_VP(a, qa, s11)
-        RC_SOB_VP(a, qb, s12)
-        RC_SOB_VP(b, qa, s21)
-        RC_SOB_VP(b, qb, s22)
-#undef RC_SOB_VP
-        const V4<R> sj = sS[u], uj = sU[u];
-        const R wr = w * rho, w0 = w * rho0;
-        const R tt = wr * (t.x * qt.x + t.y * qt.y + t.z * qt.z);
-        Wq += wr;
-        Qx += tt * sj.x;
-        Qy += tt * sj.y;
-        Qz += tt * sj.z;
-        P0 += w0;
-        Px += w0 * uj.x;
-        Py += w0 * uj.y;
-        Pz += w0 * uj.z;
-      }
+      auto sweep = [&](auto tested) {
+        for (int u = u0; u < u1; ++u) {
+          const V4<R> qa = sA[u], qb = sB[u], qt = sT[u];
+          R rho, rho0, w = qa.w;
+          if constexpr (decltype(tested)::value) {
+            const int2 ej = sE[u];
+            const bool skip = (ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y);
+            w = skip ? R(0) : w;
+            sob_edge_pair<R, EC, true>(a.x, a.y, a.z, b.x, b.y, b.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z, qb.x,
+                                       qb.y, qb.z, qt.x, qt.y, qt.z, skip ? R(1) : R(0), half_expo, rho, rho0);
+          } else {
+            sob_edge_pair<R, EC, false>(a.x, a.y, a.z, b.x, b.y, b.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z, qb.x,
+                                        qb.y, qb.z, qt.x, qt.y, qt.z, R(0), half_expo, rho, rho0);
+          }
+          const V4<R> sj = sS[u], uj = sU[u];
+          const R wr = w * rho, w0 = w * rho0;
+          const R tt = wr * (t.x * qt.x + t.y * qt.y + t.z * qt.z);
+          Wq += wr;
+          Qx = fma(tt, sj.x, Qx);
+          Qy = fma(tt, sj.y, Qy);
+          Qz = fma(tt, sj.z, Qz);
+          P0 += w0;
+          Px = fma(w0, uj.x, Px);
+          Py = fma(w0, uj.y, Py);
+          Pz = fma(w0, uj.z, Pz);
+        }
+      };
+      if (test) sweep(std::true_type{});
+      else sweep(std::false_type{});
       acc[0] += (double)Wq; acc[1] += (double)Qx; acc[2] += (double)Qy; acc[3] += (double)Qz;
       acc[4] += (double)P0; acc[5] += (double)Px; acc[6] += (double)Py; acc[7] += (double)Pz;
     }

@@ -3,6 +3,8 @@
 // accumulation of the tangent-point energy and its derivatives.
 #pragma once
 
+#include <type_traits>
+
 #include "rc_internal.h"
 
 namespace rc {
@@ -70,6 +72,31 @@ __device__ __forceinline__ R pow_sigma(R r2, R rs, R ri, R half_expo) {
   if constexpr (EC == kA2B4) return ri;                       // 2 sigma + 1 = 2
   else if constexpr (EC == kA2B45) return ri * f_sqrt<R>(rs);  // 2.5
   else return f_exp2<R>(-half_expo * f_log2<R>(r2));          // 7/3 for (3,6), general
+}
+
+// ri = r2^-1 and p = r2^(-(2 sigma + 1)/2) for one vertex pair.  In FP64 with
+// 2 sigma + 1 = 2.5 both are powers of q = r2^(-1/4) (ri = q^4, p = q^5): q
+// comes from an FP32 estimate refined by two Newton steps for q^-4 = r2,
+// q <- q + q (1 - r2 q^4) / 4, each roughly squaring the relative error of
+// the estimate (about 2^-22): no FP64 transcendental and no branch.
+template <int EC, typename R>
+__device__ __forceinline__ void sob_powers(R r2, R half_expo, R& ri, R& p) {
+  if constexpr (EC == kA2B45 && std::is_same<R, double>::value) {
+    double q = (double)__builtin_amdgcn_sqrtf(__builtin_amdgcn_rsqf((float)r2));
+    const double mr = -0.25 * r2;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const double q2 = q * q;
+      q = fma(q, fma(mr, q2 * q2, 0.25), q);
+    }
+    const double q2 = q * q;
+    ri = q2 * q2;
+    p = ri * q;
+  } else {
+    const R rs = f_rsq<R>(r2);
+    ri = rs * rs;
+    p = pow_sigma<EC, R>(r2, rs, ri, half_expo);
+  }
 }
 
 template <typename R>
@@ -224,6 +251,45 @@ __device__ __forceinline__ void tpe_edge_pair(
     Hy = fma(m1, d11y, fma(m2, d12y, Hy));
     Hz = fma(m1, d11z, fma(m2, d12z, Hz));
   }
+}
+
+// Weights of the operator A = B + B0 (Sec. 4.2.2-4.2.3) for one ordered edge
+// pair (I, J): rho = the sum over the four vertex pairs of |d|^-(2 sigma + 1),
+// rho0 = the same terms weighted by (|T x d|^2 + |U x d|^2) / |d|^4.  The
+// geometry and the shared work are those of tpe_edge_pair (two cross products
+// of each kind, T.d shifted by l_I, |d|^2 = |T x d|^2 + (T.d)^2).  skipv = 1
+// for a skipped pair keeps |d|^2 >= 1 (its weight is zeroed by the caller).
+template <typename R, int EC, bool SKIP>
+__device__ __forceinline__ void sob_edge_pair(R ax, R ay, R az, R bx, R by, R bz, R Tx, R Ty, R Tz, R lI,
+                                              R cx, R cy, R cz, R ex, R ey, R ez, R Ux, R Uy, R Uz,
+                                              R skipv, R half_expo, R& rho, R& rho0) {
+  const R d11x = ax - cx, d11y = ay - cy, d11z = az - cz;  // d(a, c)
+  const R d12x = ax - ex, d12y = ay - ey, d12z = az - ez;  // d(a, e)
+  const R d21x = bx - cx, d21y = by - cy, d21z = bz - cz;  // d(b, c)
+  R cI1 = cross_norm2<R>(Tx, Ty, Tz, d11x, d11y, d11z);
+  R cI2 = cross_norm2<R>(Tx, Ty, Tz, d12x, d12y, d12z);
+  if constexpr (SKIP) {
+    cI1 += skipv;
+    cI2 += skipv;
+  }
+  const R cJ1 = cross_norm2<R>(Ux, Uy, Uz, d11x, d11y, d11z);
+  const R cJ2 = cross_norm2<R>(Ux, Uy, Uz, d21x, d21y, d21z);
+  const R t11 = Tx * d11x + Ty * d11y + Tz * d11z;
+  const R t12 = Tx * d12x + Ty * d12y + Tz * d12z;
+  const R t21 = t11 + lI, t22 = t12 + lI;
+  const R r11 = t11 * t11 + cI1, r12 = t12 * t12 + cI2;
+  const R r21 = t21 * t21 + cI1, r22 = t22 * t22 + cI2;
+  R ri11, ri12, ri21, ri22, p11, p12, p21, p22;
+  sob_powers<EC, R>(r11, half_expo, ri11, p11);
+  sob_powers<EC, R>(r12, half_expo, ri12, p12);
+  sob_powers<EC, R>(r21, half_expo, ri21, p21);
+  sob_powers<EC, R>(r22, half_expo, ri22, p22);
+  rho = (p11 + p12) + (p21 + p22);
+  const R q11 = p11 * ri11 * ri11, q12 = p12 * ri12 * ri12, q21 = p21 * ri21 * ri21, q22 = p22 * ri22 * ri22;
+  R z = cI1 * (q11 + q21);
+  z = fma(cI2, q12 + q22, z);
+  z = fma(cJ1, q11 + q12, z);
+  rho0 = fma(cJ2, q21 + q22, z);
 }
 
 // ---------------------------------------------------------------------------
