@@ -275,22 +275,13 @@ __global__ __launch_bounds__(256) void k_assemble_lowp_ep(
       if (I != J && ei.x != ej.x && ei.x != ej.y && ei.y != ej.x && ei.y != ej.y) {
         const EpEdge& X = I < J ? ed[0][a] : ed[1][b];  // the smaller edge first
         const EpEdge& Y = I < J ? ed[1][b] : ed[0][a];
-        float rho = 0.f, rho0 = 0.f;
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y) {
-            const double* P = x ? X.b : X.a;
-            const double* Q = y ? Y.b : Y.a;
-            const float dx = (float)(P[0] - Q[0]), dy = (float)(P[1] - Q[1]), dz = (float)(P[2] - Q[2]);
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float rs_ = f_rsq<float>(r2), ri = rs_ * rs_;
-            const float pw = pow_sigma<EC, float>(r2, rs_, ri, half_expo);
-            rho += pw;
-            rho0 += pw * (cross_norm2<float>(X.t[0], X.t[1], X.t[2], dx, dy, dz) +
-                          cross_norm2<float>(Y.t[0], Y.t[1], Y.t[2], dx, dy, dz)) *
-                    ri * ri;
-          }
+        // differences taken in FP64, then rounded
+        float rho, rho0;
+        sob_edge_pair_d<float, EC, false>(
+            (float)(X.a[0] - Y.a[0]), (float)(X.a[1] - Y.a[1]), (float)(X.a[2] - Y.a[2]), (float)(X.a[0] - Y.b[0]),
+            (float)(X.a[1] - Y.b[1]), (float)(X.a[2] - Y.b[2]), (float)(X.b[0] - Y.a[0]), (float)(X.b[1] - Y.a[1]),
+            (float)(X.b[2] - Y.a[2]), X.t[0], X.t[1], X.t[2], X.l, Y.t[0], Y.t[1], Y.t[2], 0.f, half_expo, rho,
+            rho0);
         g = rho * (X.t[0] * Y.t[0] + X.t[1] * Y.t[1] + X.t[2] * Y.t[2]);
         h = X.l * Y.l * rho0;
       }

@@ -257,15 +257,13 @@ __device__ __forceinline__ void tpe_edge_pair(
 // pair (I, J): rho = the sum over the four vertex pairs of |d|^-(2 sigma + 1),
 // rho0 = the same terms weighted by (|T x d|^2 + |U x d|^2) / |d|^4.  The
 // geometry and the shared work are those of tpe_edge_pair (two cross products
-// of each kind, T.d shifted by l_I, |d|^2 = |T x d|^2 + (T.d)^2).  skipv = 1
-// for a skipped pair keeps |d|^2 >= 1 (its weight is zeroed by the caller).
+// of each kind, T.d shifted by l_I, |d|^2 = |T x d|^2 + (T.d)^2); this core
+// takes the differences d(a, c), d(a, e) and d(b, c).  skipv = 1 for a
+// skipped pair keeps |d|^2 >= 1 (its weight is zeroed by the caller).
 template <typename R, int EC, bool SKIP>
-__device__ __forceinline__ void sob_edge_pair(R ax, R ay, R az, R bx, R by, R bz, R Tx, R Ty, R Tz, R lI,
-                                              R cx, R cy, R cz, R ex, R ey, R ez, R Ux, R Uy, R Uz,
-                                              R skipv, R half_expo, R& rho, R& rho0) {
-  const R d11x = ax - cx, d11y = ay - cy, d11z = az - cz;  // d(a, c)
-  const R d12x = ax - ex, d12y = ay - ey, d12z = az - ez;  // d(a, e)
-  const R d21x = bx - cx, d21y = by - cy, d21z = bz - cz;  // d(b, c)
+__device__ __forceinline__ void sob_edge_pair_d(R d11x, R d11y, R d11z, R d12x, R d12y, R d12z, R d21x, R d21y,
+                                                R d21z, R Tx, R Ty, R Tz, R lI, R Ux, R Uy, R Uz, R skipv,
+                                                R half_expo, R& rho, R& rho0) {
   R cI1 = cross_norm2<R>(Tx, Ty, Tz, d11x, d11y, d11z);
   R cI2 = cross_norm2<R>(Tx, Ty, Tz, d12x, d12y, d12z);
   if constexpr (SKIP) {
@@ -290,6 +288,15 @@ __device__ __forceinline__ void sob_edge_pair(R ax, R ay, R az, R bx, R by, R bz
   z = fma(cI2, q12 + q22, z);
   z = fma(cJ1, q11 + q12, z);
   rho0 = fma(cJ2, q21 + q22, z);
+}
+
+// The same from the endpoints: target a, b (tangent T, length l_I), source c, e (tangent U).
+template <typename R, int EC, bool SKIP>
+__device__ __forceinline__ void sob_edge_pair(R ax, R ay, R az, R bx, R by, R bz, R Tx, R Ty, R Tz, R lI,
+                                              R cx, R cy, R cz, R ex, R ey, R ez, R Ux, R Uy, R Uz,
+                                              R skipv, R half_expo, R& rho, R& rho0) {
+  sob_edge_pair_d<R, EC, SKIP>(ax - cx, ay - cy, az - cz, ax - ex, ay - ey, az - ez, bx - cx, by - cy, bz - cz, Tx,
+                               Ty, Tz, lI, Ux, Uy, Uz, skipv, half_expo, rho, rho0);
 }
 
 // ---------------------------------------------------------------------------
