@@ -98,6 +98,14 @@ struct ProjData {
   const double* prev = nullptr;  // null: no beta term (prev may alias out)
   double* xacc = nullptr;        // also xacc = out (xset) or xacc += out, per entry
   bool xset = false;
+  // optional: also the operand of the next 16-bit product taken of out (of
+  // xacc when prep_x), in the difference form of that product's preparation:
+  // pp [nkt][3][32] = sqrt(d_v) (x_v - x_head), pcref [nkt][3] = x_head, the
+  // head being the first vertex of v's 32-vertex column tile
+  float* pp = nullptr;
+  double* pcref = nullptr;
+  const double* psqd = nullptr;
+  bool prep_x = false;
 };
 void cons_project_fused(const ProjData& d, const double* in, double* out, hipStream_t s);
 void cons_project_pack(const double* geo, const int2* edges, const int* path_edge, int np, const int* inc_off,

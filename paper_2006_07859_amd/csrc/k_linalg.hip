@@ -887,11 +887,32 @@ __global__ __launch_bounds__(kSpThreads) void k_proj_solve(const ProjData d, int
   }
 }
 
+// The product operand of d.pp for the workgroup's vertices (NT threads, the
+// first vertex a multiple of 32, one vertex per thread): the tile heads are
+// exchanged through LDS.  Every thread of the workgroup must call it.
+template <int NT>
+__device__ __forceinline__ void proj_prep_operand(const ProjData& d, int v, bool vert, const double (&val)[3]) {
+  __shared__ double heads[NT / 32][3];
+  const int lt = threadIdx.x;
+  if (vert && lt % 32 == 0)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) heads[lt / 32][cc] = val[cc];
+  __syncthreads();
+  if (!vert) return;
+  const int kt = v / 32, j = v % 32;
+  const double sq = d.psqd[v];
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    const double h = heads[lt / 32][cc];
+    d.pp[(size_t)kt * 96 + cc * 32 + j] = (float)(sq * (val[cc] - h));
+    if (j == 0) d.pcref[kt * 3 + cc] = h;
+  }
+}
+
 // out_v = in_v - [ sum_{path rows k at v} s(v) T_I (yp_k - (Z yb)_k) + sum_r yb[r] rows[r][v] ]
-__global__ __launch_bounds__(256) void k_apply_CT_z(const ProjData d, const double* __restrict__ in,
-                                                    double* __restrict__ out) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= d.nV) return;
+// for vertex v (the body of k_apply_CT_z); val receives out_v (xacc_v when prep_x).
+__device__ __forceinline__ void apply_CT_z_vertex(const ProjData& d, int v, const double* __restrict__ in,
+                                                  double* __restrict__ out, double (&val)[3]) {
   const int np = d.np, nb = d.nb;
   const TriBlocks& L = d.tri;
   double ybr[kProjMaxBorder];
@@ -934,7 +955,62 @@ __global__ __launch_bounds__(256) void k_apply_CT_z(const ProjData d, const doub
     const double o0 = sw * (in[3 * v + cc] - acc[cc]);
     const double o = d.prev ? d.beta * d.prev[3 * v + cc] + o0 : o0;
     out[3 * v + cc] = o;
-    if (d.xacc) d.xacc[3 * v + cc] = d.xset ? o : d.xacc[3 * v + cc] + o;
+    val[cc] = o;
+    if (d.xacc) {
+      const double xa = d.xset ? o : d.xacc[3 * v + cc] + o;
+      d.xacc[3 * v + cc] = xa;
+      if (d.prep_x) val[cc] = xa;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_apply_CT_z(const ProjData d, const double* __restrict__ in,
+                                                    double* __restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool vert = v < d.nV;
+  double val[3] = {0.0, 0.0, 0.0};
+  if (vert) apply_CT_z_vertex(d, v, in, out, val);
+  if (d.pp) proj_prep_operand<256>(d, v, vert, val);
+}
+
+// The last step of k_proj_small for vertex t; val receives out_t (xacc_t when prep_x).
+__device__ __forceinline__ void proj_small_vertex(const ProjData& d, int t, double* __restrict__ out,
+                                                  const ProjVert& pv, double w_t, double x0, double x1, double x2,
+                                                  const double* yps, const double* ybs, double (&val)[3]) {
+  const int np = d.np, nV = d.nV, nb = d.nb;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int p = pv.row[q];
+    if (p < 0) continue;
+    double y = yps[p];
+#pragma unroll
+    for (int r = 0; r < kProjMaxBorder; ++r)
+      if (r < nb) y -= d.Z[(size_t)r * np + p] * ybs[r];
+    a0 += pv.c[q][0] * y;
+    a1 += pv.c[q][1] * y;
+    a2 += pv.c[q][2] * y;
+  }
+#pragma unroll
+  for (int r = 0; r < kProjMaxBorder; ++r)
+    if (r < nb) {
+      const double* rv = d.rows + ((size_t)r * nV + t) * 3;
+      a0 += ybs[r] * rv[0];
+      a1 += ybs[r] * rv[1];
+      a2 += ybs[r] * rv[2];
+    }
+  const double sw = d.scale * w_t;
+  double o[3] = {sw * (x0 - a0), sw * (x1 - a1), sw * (x2 - a2)};
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    if (d.prev) o[cc] += d.beta * d.prev[3 * t + cc];
+    out[3 * t + cc] = o[cc];
+    val[cc] = o[cc];
+    if (d.xacc) {
+      const double xa = d.xset ? o[cc] : d.xacc[3 * t + cc] + o[cc];
+      d.xacc[3 * t + cc] = xa;
+      if (d.prep_x) val[cc] = xa;
+    }
   }
 }
 
@@ -1021,37 +1097,11 @@ __global__ __launch_bounds__(kTriThreads) void k_proj_small(const ProjData d, co
     if (row) yps[t] = -c_t * ui_t * B + z * ui_t;
   }
   __syncthreads();
-  if (!vert) return;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int p = pv.row[q];
-    if (p < 0) continue;
-    double y = yps[p];
-#pragma unroll
-    for (int r = 0; r < kProjMaxBorder; ++r)
-      if (r < nb) y -= d.Z[(size_t)r * np + p] * ybs[r];
-    a0 += pv.c[q][0] * y;
-    a1 += pv.c[q][1] * y;
-    a2 += pv.c[q][2] * y;
-  }
-#pragma unroll
-  for (int r = 0; r < kProjMaxBorder; ++r)
-    if (r < nb) {
-      const double* rv = d.rows + ((size_t)r * nV + t) * 3;
-      a0 += ybs[r] * rv[0];
-      a1 += ybs[r] * rv[1];
-      a2 += ybs[r] * rv[2];
-    }
-  const double sw = d.scale * w_t;
-  double o[3] = {sw * (x0 - a0), sw * (x1 - a1), sw * (x2 - a2)};
-#pragma unroll
-  for (int cc = 0; cc < 3; ++cc) {
-    if (d.prev) o[cc] += d.beta * d.prev[3 * t + cc];
-    out[3 * t + cc] = o[cc];
-    if (d.xacc) d.xacc[3 * t + cc] = d.xset ? o[cc] : d.xacc[3 * t + cc] + o[cc];
-  }
+  double val[3] = {0.0, 0.0, 0.0};
+  if (vert) proj_small_vertex(d, t, out, pv, w_t, x0, x1, x2, yps, ybs, val);
+  if (d.pp) proj_prep_operand<kTriThreads>(d, t, vert, val);
 }
+
 
 void cons_project_fused(const ProjData& d, const double* in, double* out, hipStream_t s) {
   if (d.prow && d.pvert && d.np <= kTriThreads && d.nV <= kTriThreads && d.tri.B == 1) {

@@ -436,6 +436,19 @@ __global__ void k_lowp_prep(const double* __restrict__ X, const double* __restri
   if (c == 0) sqdf[kt * 32 + j] = w < n ? (float)sqd[w] : 0.f;
 }
 
+// The parts of the operand that depend on the assembly only: sqdf, and p = 0
+// for the padding columns w >= n (an operand written by another launch covers
+// the vertices w < n).
+__global__ void k_lowp_prep_static(const double* __restrict__ sqd, int n, int nkt, float* __restrict__ p,
+                                   float* __restrict__ sqdf) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // (kt, c, j)
+  if (idx >= nkt * 96) return;
+  const int kt = idx / 96, c = (idx / 32) % 3, j = idx % 32;
+  const int w = kt * 32 + j;
+  if (w >= n) p[idx] = 0.f;
+  if (c == 0) sqdf[kt * 32 + j] = w < n ? (float)sqd[w] : 0.f;
+}
+
 // out[0] = 2 max|x| max sqrt(d): a bound of |sqrt(d_w) (x_w - c)| (one workgroup).
 __global__ __launch_bounds__(1024) void k_lowp_absmax(const double* __restrict__ X, const double* __restrict__ sqd,
                                                       int n, double* __restrict__ out) {
@@ -842,6 +855,8 @@ rc_status launch_assemble_lowp(const Curve& c, LowpOp& op, int fmt, int band, bo
   if (with32)
     hipLaunchKernelGGL(k_lowp_sigma, dim3(cdiv(op.n, 256)), dim3(256), 0, s, op.rowpart32, op.ngroups, bp, op.sqd,
                        op.n, op.sigma32, (double*)nullptr);
+  hipLaunchKernelGGL(k_lowp_prep_static, dim3(cdiv(op.nkt * 96, 256)), dim3(256), 0, s, op.sqd, op.n, op.nkt, op.pbuf,
+                     op.sqdf);
   RC_HIP(hipGetLastError());
   op.ready = true;
   return RC_OK;
@@ -854,12 +869,12 @@ static void prep(const LowpOp& op, const double* X, hipStream_t s) {
 
 template <typename T>
 static void apply16(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer,
-                    const double* base, double alpha) {
+                    const double* base, double alpha, bool prepped) {
   typedef typename Vec8<T>::type V;
   // FP16 operands need the power-of-two scaling into range; BF16 ones do not
   const double* mx = std::is_same<T, _Float16>::value ? (const double*)op.mx : nullptr;
   if (mx) hipLaunchKernelGGL(k_lowp_absmax, dim3(1), dim3(1024), 0, s, X, op.sqd, op.n, op.mx);
-  prep(op, X, s);
+  if (!prepped) prep(op, X, s);
   const int waves = cdiv(op.nrb, kLowpRB) * op.nsplit;
   if (timer) timer->mark(timer->lowp, s);
   hipLaunchKernelGGL((k_lowp_gemv<T, kLowpRB>), dim3(cdiv(waves, 4)), dim3(256), 0, s, (const V*)op.tiles,
@@ -871,14 +886,14 @@ static void apply16(const LowpOp& op, const double* X, double* Y, hipStream_t s,
 }
 
 rc_status launch_lowp_apply(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer,
-                            const double* base, double alpha) {
+                            const double* base, double alpha, bool prepped) {
   if (!op.ready) {
     set_error("the assembled operator has not been built");
     return RC_ERR_ARG;
   }
   KernelTimer* t = (timer && timer->on) ? timer : nullptr;
-  if (op.fmt == 1) apply16<__bf16>(op, X, Y, s, t, base, alpha);
-  else apply16<_Float16>(op, X, Y, s, t, base, alpha);
+  if (op.fmt == 1) apply16<__bf16>(op, X, Y, s, t, base, alpha, prepped);
+  else apply16<_Float16>(op, X, Y, s, t, base, alpha, prepped);
   RC_HIP(hipGetLastError());
   return RC_OK;
 }

@@ -235,8 +235,10 @@ rc_status launch_assemble_lowp(const Curve& c, LowpOp& op, int fmt, int band, bo
 // Y = A^ X with the 16-bit block (apply) or the FP32 block (apply32); X and Y
 // [nV][3] FP64.  The product kernels are timed when the timer is on.
 // Y = A X, or Y = base + alpha A X when base is given (Y may alias base).
+// prepped: the product's operand (pbuf, cref) already holds X in its
+// difference form, written by the launch that produced X.
 rc_status launch_lowp_apply(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer,
-                            const double* base = nullptr, double alpha = 1.0);
+                            const double* base = nullptr, double alpha = 1.0, bool prepped = false);
 rc_status launch_lowp_apply32(const LowpOp& op, const double* X, double* Y, hipStream_t s, KernelTimer* timer);
 
 // Learned multilevel preconditioner (k_learn.hip): the MLP and the features.

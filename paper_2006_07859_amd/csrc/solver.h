@@ -176,7 +176,10 @@ bool trace_on();
 rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask);
 void cons_free(Cons& k);
 rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma, const double* w = nullptr);
-void cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double* out, double* xacc = nullptr);
+// With pop, the last launch also writes the operand of pop's next product,
+// taken of out (of xacc when pfrom_x); returns whether it did.
+bool cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double* out, double* xacc = nullptr,
+                  const LowpOp* pop = nullptr, bool pfrom_x = false);
 void cons_values(rc_ctx* c, const double* gamma, double* phi);
 rc_status cons_set_targets(rc_ctx* c, const double* gamma_ref, const double* x0_h, double total_len0,
                            const double* edge_len0);

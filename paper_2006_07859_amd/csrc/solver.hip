@@ -415,13 +415,24 @@ static ProjData proj_data(const Curve& cv, Cons& k) {
   return d;
 }
 
+// Points a projection's last launch at the operand of pop's next product.
+static void set_prep(ProjData& d, const LowpOp* pop, bool pfrom_x) {
+  if (!pop) return;
+  d.pp = pop->pbuf;
+  d.pcref = pop->cref;
+  d.psqd = pop->sqd;
+  d.prep_x = pfrom_x;
+}
+
 // out = beta prev + scale M in with M = W - W C^T (C W C^T)^-1 C W, W = diag(w):
 // kw holds the factors of C W C^T (cons_prepare with w); nb <= kProjMaxBorder.
-// With xacc, also xacc = out (xset) or xacc += out.
+// With xacc, also xacc = out (xset) or xacc += out.  With pop, also the
+// operand of pop's next product (of out, or of xacc when pfrom_x).
 static void cons_project_w(rc_ctx* c, const Curve& cv, Cons& kw, const double* w, const double* in, double* out,
                            double scale, double beta, const double* prev, double* xacc = nullptr,
-                           bool xset = false) {
+                           bool xset = false, const LowpOp* pop = nullptr, bool pfrom_x = false) {
   ProjData d = proj_data(cv, kw);
+  set_prep(d, pop, pfrom_x);
   d.w = w;
   d.scale = scale;
   d.beta = beta;
@@ -433,25 +444,28 @@ static void cons_project_w(rc_ctx* c, const Curve& cv, Cons& kw, const double* w
 
 // out = P in with P = I - C^T (C C^T)^-1 C (in may equal out); with xacc, also
 // xacc += out.
-void cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double* out, double* xacc) {
+bool cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double* out, double* xacc,
+                  const LowpOp* pop, bool pfrom_x) {
   hipStream_t s = c->stream;
   const int nV = cv.nV;
   if (k.k == 0) {
     if (in != out) vec_copy(in, out, 3 * nV, s);
     if (xacc) vec_axpby(1.0, out, 1.0, xacc, 3 * nV, s);
-    return;
+    return false;
   }
   if (k.nb <= kProjMaxBorder) {
     ProjData d = proj_data(cv, k);
     d.xacc = xacc;
+    set_prep(d, pop, pfrom_x);
     cons_project_fused(d, in, out, s);
-    return;
+    return pop != nullptr;
   }
   cons_path_apply(k.geo, cv.edges, k.path_edge, k.np, in, nV, 1, k.wp, s);
   if (k.nb > 0) vec_dots(k.rows, 3 * nV, in, 0, 3 * nV, k.nb, c->red, k.wb, s);
   cons_solve_K(c, k);
   cons_apply_CT(k.geo, cv.inc_off, cv.inc, k.edge_path_row, k.yp, k.rows, k.yb, k.nb, nV, in, out, s);
   if (xacc) vec_axpby(1.0, out, 1.0, xacc, 3 * nV, s);
+  return false;
 }
 
 // z = C^T (C C^T)^-1 b for an external-order b (finest level).
@@ -813,7 +827,13 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
 }
 
 // Projected Chebyshev smoothing of P A_l P x = b (b in range(P)) on level l.
-static rc_status cheb_smooth(rc_ctx* c, int l, double* x, const double* b, bool x_zero) {
+// Chebyshev smoothing of A x = b at level l.  x_prepped: the 16-bit operand
+// of the level already holds x (written by the launch that produced it);
+// prep_after: the caller's next product is of x, so the last projection writes
+// its operand, and *prepped_out tells whether it did.
+static rc_status cheb_smooth(rc_ctx* c, int l, double* x, const double* b, bool x_zero, bool x_prepped = false,
+                             bool prep_after = false, bool* prepped_out = nullptr) {
+  if (prepped_out) *prepped_out = false;
   const Curve& cv = level_curve(c, l);
   Cons& K = level_cons(c, l);
   MGLevelState& st = c->mg[l];
@@ -829,29 +849,36 @@ static rc_status cheb_smooth(rc_ctx* c, int l, double* x, const double* b, bool 
     // r = base - A X is formed by the product's finish (the 16-bit block) and
     // x += d by the projector's last launch.
     Cons& Kw = level_cons_w(c, l);
-    auto residual = [&](const double* X, const double* base) -> rc_status {  // r = base - A X
-      if (l < c->lowp_levels)
-        return launch_lowp_apply(level_lowp(c, l), X, st.r, s, l == 0 ? &c->timer : nullptr, base, -1.0);
+    // the 16-bit block of the level; its operand is written by the projection
+    // before each product (of d, or of x for the caller's next product)
+    const LowpOp* lop = l < c->lowp_levels ? &level_lowp(c, l) : nullptr;
+    const int deg = c->cheb_deg;
+    auto residual = [&](const double* X, const double* base, bool prepped) -> rc_status {  // r = base - A X
+      if (lop) return launch_lowp_apply(*lop, X, st.r, s, l == 0 ? &c->timer : nullptr, base, -1.0, prepped);
       RC_TRY(apply_level(c, l, X, st.t));
       if (base != st.r) vec_copy(base, st.r, n3, s);
       vec_axpby(-1.0, st.t, 1.0, st.r, n3, s);
       return RC_OK;
     };
+    // the operand the k-th projection (k = 0 .. deg - 1) writes: d when a residual of d follows, else x
+    auto prep_op = [&](int k) -> const LowpOp* { return (k + 1 < deg || prep_after) ? lop : nullptr; };
     if (x_zero) {  // d = M b / theta, x = d
-      cons_project_w(c, cv, Kw, st.w, b, st.d, 1.0 / theta, 0.0, nullptr, x, true);
-      if (c->cheb_deg > 1) RC_TRY(residual(st.d, b));
+      cons_project_w(c, cv, Kw, st.w, b, st.d, 1.0 / theta, 0.0, nullptr, x, true, prep_op(0), deg == 1);
+      if (deg > 1) RC_TRY(residual(st.d, b, lop != nullptr));
     } else {  // r = b - A x, d = M r / theta, x += d
-      RC_TRY(residual(x, b));
-      cons_project_w(c, cv, Kw, st.w, st.r, st.d, 1.0 / theta, 0.0, nullptr, x, false);
-      if (c->cheb_deg > 1) RC_TRY(residual(st.d, st.r));
+      RC_TRY(residual(x, b, x_prepped && lop != nullptr));
+      cons_project_w(c, cv, Kw, st.w, st.r, st.d, 1.0 / theta, 0.0, nullptr, x, false, prep_op(0), deg == 1);
+      if (deg > 1) RC_TRY(residual(st.d, st.r, lop != nullptr));
     }
-    for (int k = 1; k < c->cheb_deg; ++k) {
+    for (int k = 1; k < deg; ++k) {
       const double rn = 1.0 / (2.0 * sigma - rho);
       // d = c1 d + c2 M r, x += d
-      cons_project_w(c, cv, Kw, st.w, st.r, st.d, 2.0 * rn / delta, rn * rho, st.d, x, false);
+      cons_project_w(c, cv, Kw, st.w, st.r, st.d, 2.0 * rn / delta, rn * rho, st.d, x, false, prep_op(k),
+                     k + 1 == deg);
       rho = rn;
-      if (k + 1 < c->cheb_deg) RC_TRY(residual(st.d, st.r));
+      if (k + 1 < deg) RC_TRY(residual(st.d, st.r, lop != nullptr));
     }
+    if (prepped_out) *prepped_out = prep_after && lop != nullptr;
     return RC_OK;
   }
   if (x_zero) {
@@ -892,9 +919,11 @@ static rc_status vcycle(rc_ctx* c, int l, const double* b, double* x) {
   Cons& K = level_cons(c, l);
   MGLevelState& st = c->mg[l];
   const int n3 = 3 * cv.nV;
-  RC_TRY(cheb_smooth(c, l, x, b, true));
-  if (l < c->lowp_levels) {  // t = b - A x
-    RC_TRY(launch_lowp_apply(level_lowp(c, l), x, st.t, s, l == 0 ? &c->timer : nullptr, b, -1.0));
+  const bool lp = l < c->lowp_levels;
+  bool prepped = false;
+  RC_TRY(cheb_smooth(c, l, x, b, true, false, lp, &prepped));
+  if (lp) {  // t = b - A x
+    RC_TRY(launch_lowp_apply(level_lowp(c, l), x, st.t, s, l == 0 ? &c->timer : nullptr, b, -1.0, prepped));
   } else {
     RC_TRY(apply_level(c, l, x, st.t));
     vec_axpby(1.0, b, -1.0, st.t, n3, s);
@@ -910,8 +939,9 @@ static rc_status vcycle(rc_ctx* c, int l, const double* b, double* x) {
   if (!c->mg_weighted) cons_project(c, C.curve, C.cons, sc.b, sc.b);
   RC_TRY(vcycle(c, l + 1, sc.b, sc.x));
   hipLaunchKernelGGL(k_prolong, dim3(cdiv(cv.nV, 256)), dim3(256), 0, s, C.prolong, cv.nV, sc.x, st.t);
-  cons_project(c, cv, K, st.t, st.t, x);  // x += P J x_c
-  RC_TRY(cheb_smooth(c, l, x, b, false));
+  // x += P J x_c (writing the operand of the smoother's first product, A x)
+  const bool xp = cons_project(c, cv, K, st.t, st.t, x, (lp && c->mg_weighted) ? &level_lowp(c, l) : nullptr, true);
+  RC_TRY(cheb_smooth(c, l, x, b, false, xp));
   return RC_OK;
 }
 
