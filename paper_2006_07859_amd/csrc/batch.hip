@@ -397,6 +397,29 @@ __global__ void k_b_blocks(const V4<double>* __restrict__ GA, const V4<double>* 
 // (one workgroup per tile), so a step runs on the whole GPU.
 constexpr int kGT = 32;
 
+// Scalar Gauss-Jordan of a diagonal tile in LDS (rows and columns >= kk hold
+// the identity), by a workgroup of 256 threads; info is raised when a pivot is
+// not positive.  Begins and ends with the tile visible to the whole workgroup.
+__device__ __forceinline__ void gj_tile_invert(double (&D)[kGT][kGT + 1], double (&f)[kGT], int kk, int* info) {
+  const int tid = threadIdx.x;
+  for (int p = 0; p < kGT; ++p) {
+    if (info && tid == 0 && p < kk && !(D[p][p] > 0.0)) atomicMax(info, 1);  // not positive definite
+    const double ip = 1.0 / D[p][p];
+    __syncthreads();
+    if (tid < kGT) {
+      f[tid] = tid == p ? 0.0 : D[tid][p];
+      D[p][tid] = (tid == p ? 1.0 : D[p][tid]) * ip;
+    }
+    __syncthreads();
+    for (int e = tid; e < kGT * kGT; e += 256) {
+      const int r = e / kGT, c = e % kGT;
+      if (r == p) continue;
+      D[r][c] = (c == p) ? -f[r] * D[p][p] : D[r][c] - f[r] * D[p][c];
+    }
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(256) void k_gj_panel(int k, const int* __restrict__ list,
                                                   const int* __restrict__ chain_voff,
                                                   const long long* __restrict__ blk_off, double* __restrict__ Minv,
@@ -419,23 +442,7 @@ __global__ __launch_bounds__(256) void k_gj_panel(int k, const int* __restrict__
     Sq[e] = c < kk ? M[(size_t)i * m + r0 + c] : 0.0;
   }
   __syncthreads();
-  // scalar Gauss-Jordan of the diagonal tile in LDS
-  for (int p = 0; p < kGT; ++p) {
-    if (info && tid == 0 && p < kk && !(D[p][p] > 0.0)) atomicMax(info, 1);  // not positive definite
-    const double ip = 1.0 / D[p][p];
-    __syncthreads();
-    if (tid < kGT) {
-      f[tid] = tid == p ? 0.0 : D[tid][p];
-      D[p][tid] = (tid == p ? 1.0 : D[p][tid]) * ip;
-    }
-    __syncthreads();
-    for (int e = tid; e < kGT * kGT; e += 256) {
-      const int r = e / kGT, c = e % kGT;
-      if (r == p) continue;
-      D[r][c] = (c == p) ? -f[r] * D[p][p] : D[r][c] - f[r] * D[p][c];
-    }
-    __syncthreads();
-  }
+  gj_tile_invert(D, f, kk, info);
   // row panel: A_kj <- Dinv A_kj for the columns outside tile k
   for (int c = tid; c < m; c += 256) {
     if (c >= r0 && c < r0 + kk) continue;
@@ -499,6 +506,56 @@ __global__ __launch_bounds__(256) void k_gj_update(int k, const int* __restrict_
   }
 }
 
+// The panel step of one large matrix over many workgroups: k_gj_diag inverts
+// the diagonal tile (one workgroup) into dinv [kGT][kGT]; k_gj_rowcol saves
+// the old column panel of rows [256 b, 256 b + 256) and forms the row panel
+// of columns [256 b, 256 b + 256) in workgroup b; the workgroup whose rows hold
+// the diagonal tile writes its inverse after saving those rows, so no
+// workgroup reads a tile another one writes.
+__global__ __launch_bounds__(256) void k_gj_diag(int k, const double* __restrict__ M, int m,
+                                                 double* __restrict__ dinv, int* __restrict__ info) {
+  __shared__ double D[kGT][kGT + 1];
+  __shared__ double f[kGT];
+  const int r0 = k * kGT, kk = min(kGT, m - r0);
+  for (int e = threadIdx.x; e < kGT * kGT; e += 256) {
+    const int r = e / kGT, c = e % kGT;
+    D[r][c] = (r < kk && c < kk) ? M[(size_t)(r0 + r) * m + r0 + c] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  gj_tile_invert(D, f, kk, info);
+  for (int e = threadIdx.x; e < kGT * kGT; e += 256) dinv[e] = D[e / kGT][e % kGT];
+}
+
+__global__ __launch_bounds__(256) void k_gj_rowcol(int k, double* __restrict__ M, int m,
+                                                   const double* __restrict__ dinv, double* __restrict__ S) {
+  __shared__ double D[kGT][kGT + 1];
+  const int tid = threadIdx.x, b = blockIdx.x;
+  const int r0 = k * kGT, kk = min(kGT, m - r0);
+  for (int e = tid; e < kGT * kGT; e += 256) D[e / kGT][e % kGT] = dinv[e];
+  for (int e = tid; e < 256 * kGT; e += 256) {  // the old column panel
+    const int i = b * 256 + e / kGT, c = e % kGT;
+    if (i < m) S[(size_t)i * kGT + c] = c < kk ? M[(size_t)i * m + r0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int c = b * 256 + tid;  // row panel: A_kj <- Dinv A_kj for the columns outside tile k
+  if (c < m && !(c >= r0 && c < r0 + kk)) {
+    double col[kGT];
+#pragma unroll
+    for (int s2 = 0; s2 < kGT; ++s2) col[s2] = s2 < kk ? M[(size_t)(r0 + s2) * m + c] : 0.0;
+    for (int r = 0; r < kk; ++r) {
+      double a = 0.0;
+#pragma unroll
+      for (int s2 = 0; s2 < kGT; ++s2) a += D[r][s2] * col[s2];
+      M[(size_t)(r0 + r) * m + c] = a;
+    }
+  }
+  if (r0 / 256 == b)  // the diagonal tile, after this workgroup saved its rows
+    for (int e = tid; e < kk * kk; e += 256) {
+      const int r = e / kk, cc = e % kk;
+      M[(size_t)(r0 + r) * m + r0 + cc] = D[r][cc];
+    }
+}
+
 // One block's bookkeeping for the blocked Gauss-Jordan: list {0}, offsets
 // {0, m}, tile prefix {0}, block offset {0}.
 __global__ void k_gj_single_meta(int m, int* __restrict__ meta, long long* __restrict__ off) {
@@ -514,9 +571,10 @@ void gj_invert_spd(double* M, int m, int* meta, long long* off, double* col, int
   if (m <= 0) return;
   hipLaunchKernelGGL(k_gj_single_meta, dim3(1), dim3(1), 0, s, m, meta, off);
   const int nb = (m + kGT - 1) / kGT;
+  double* dinv = col + (size_t)kGT * m;
   for (int k = 0; k < nb; ++k) {
-    hipLaunchKernelGGL(k_gj_panel, dim3(1), dim3(256), 0, s, k, (const int*)meta, (const int*)(meta + 1),
-                       (const long long*)off, M, col, info);
+    hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, s, k, (const double*)M, m, dinv, info);
+    hipLaunchKernelGGL(k_gj_rowcol, dim3(cdiv(m, 256)), dim3(256), 0, s, k, M, m, (const double*)dinv, col);
     hipLaunchKernelGGL(k_gj_update, dim3(nb * nb), dim3(256), 0, s, k, (const int*)meta, (const int*)(meta + 3), 1,
                        (const int*)(meta + 1), (const long long*)off, M, (const double*)col);
   }

@@ -276,7 +276,7 @@ void vec_scale_diag_inv(const double* r, const double* d, double* z, int nV, hip
 void vec_dot(const double* x, const double* y, int n, double* scratch, double* result, hipStream_t s);
 // In-place inverse of an m x m symmetric positive definite matrix (row major)
 // by blocked Gauss-Jordan with 32 x 32 tiles (batch.hip); meta: device int[4],
-// off: device long long[1], col: device double[32 m] scratch; info: device int,
+// off: device long long[1], col: device double[32 m + 1024] scratch; info: device int,
 // nonzero when a pivot is not positive.
 void gj_invert_spd(double* M, int m, int* meta, long long* off, double* col, int* info, hipStream_t s);
 // C = A B (+ beta C): small dense FP64 GEMM, row-major, all device.

@@ -540,7 +540,7 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
     RC_TRY(dalloc(&d.info, 2));
     RC_TRY(dalloc(&d.gjm, 4));
     RC_TRY(dalloc(&d.gjo, 1));
-    RC_TRY(dalloc(&d.gjc, (size_t)32 * std::max(n, kk)));
+    RC_TRY(dalloc(&d.gjc, (size_t)32 * std::max(n, kk) + 1024));
   }
   RC_TRY(launch_geometry(cv, gamma, RC_F32, s));
   RC_TRY(launch_assemble_dense(cv, c->alpha, c->beta, d.A, s));
