@@ -297,24 +297,50 @@ __global__ void k_tpe_band(const V4<double>* __restrict__ GA, const V4<double>* 
   }
 }
 
+// Sums over the partial-sum chunks of ns <= NS slots for the 64 edges of a
+// workgroup of 256 threads (edge I = 64 blockIdx.x + lane): wave g sums the
+// chunks g, g + 4, ... below nc, the four partial sums are added in wave
+// order and then the chunk band_chunk (when >= 0).  Every thread must call
+// it; the sums are returned in wave 0.
+template <int NS>
+__device__ __forceinline__ void sum_chunks4(const double* __restrict__ part, int nc, int band_chunk, int ns, int nE,
+                                            int I, bool valid, double (&s)[NS]) {
+  __shared__ double red[3][NS][64];
+  const int g = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) s[k] = 0.0;
+  if (valid)
+    for (int c = g; c < nc; c += 4)
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (k < ns) s[k] += part[((size_t)c * ns + k) * nE + I];
+  if (g > 0)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) red[g - 1][k][lane] = s[k];
+  __syncthreads();
+  if (g == 0)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      s[k] = ((s[k] + red[0][k][lane]) + red[1][k][lane]) + red[2][k][lane];
+      if (valid && k < ns && band_chunk >= 0) s[k] += part[((size_t)band_chunk * ns + k) * nE + I];
+    }
+}
+
 // Sum the chunks and turn the accumulators into per-edge energy and endpoint
 // partials: edge_out[I] = (E_I, dE/dg_i1 (3), dE/dg_i2 (3), -).
 // Chunks 0 .. n - 1 with n = nch_e[I] (batch) or nchunk, then the near-band
-// chunk `band_chunk` when it is >= 0.
-__global__ void k_tpe_finalize(const double* __restrict__ part, int nchunk, const int* __restrict__ nch_e,
-                               int band_chunk, int nE, int grad, const double* __restrict__ gd_a,
-                               const double* __restrict__ gd_t, double* __restrict__ edge_out) {
-  int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nE) return;
+// chunk `band_chunk` when it is >= 0.  64 edges per workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_tpe_finalize(const double* __restrict__ part, int nchunk,
+                                                      const int* __restrict__ nch_e, int band_chunk, int nE, int grad,
+                                                      const double* __restrict__ gd_a,
+                                                      const double* __restrict__ gd_t, double* __restrict__ edge_out) {
+  const int I = blockIdx.x * 64 + threadIdx.x % 64;
+  const bool valid = I < nE;
   const int NS = grad ? kTpeSlots : 1;
-  const int nc = nch_e ? nch_e[I] : nchunk;
+  const int nc = valid ? (nch_e ? nch_e[I] : nchunk) : 0;
   double s[kTpeSlots];
-  for (int k = 0; k < NS; ++k) {
-    double v = 0.0;
-    for (int c = 0; c < nc; ++c) v += part[((size_t)c * NS + k) * nE + I];
-    if (band_chunk >= 0) v += part[((size_t)band_chunk * NS + k) * nE + I];
-    s[k] = v;
-  }
+  sum_chunks4<kTpeSlots>(part, nc, band_chunk, NS, nE, I, valid, s);
+  if (threadIdx.x >= 64 || !valid) return;
   const double l = gd_a[4 * I + 3];
   double* o = edge_out + 8 * (size_t)I;
   o[0] = l * s[0];
@@ -516,18 +542,16 @@ __global__ __launch_bounds__(kTile) void k_sob_items(
 
 // Per edge: endpoint contributions of B u + B0 u (3 comps each) and the
 // diagonal pieces.  edge_out[I] = (y_i1 (3), y_i2 (3), dg_B, dg_B0).
-__global__ void k_sob_finalize(const double* __restrict__ part, int nchunk, const int* __restrict__ nch_e, int nE,
-                               const double* __restrict__ X, const int2* __restrict__ edges,
-                               double* __restrict__ edge_out) {
-  int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nE) return;
-  const int nc = nch_e ? nch_e[I] : nchunk;
+__global__ __launch_bounds__(256) void k_sob_finalize(const double* __restrict__ part, int nchunk,
+                                                      const int* __restrict__ nch_e, int nE,
+                                                      const double* __restrict__ X, const int2* __restrict__ edges,
+                                                      double* __restrict__ edge_out) {
+  const int I = blockIdx.x * 64 + threadIdx.x % 64;  // 64 edges per workgroup of 256 threads
+  const bool valid = I < nE;
+  const int nc = valid ? (nch_e ? nch_e[I] : nchunk) : 0;
   double s[kSobSlots];
-  for (int k = 0; k < kSobSlots; ++k) {
-    double v = 0.0;
-    for (int c = 0; c < nc; ++c) v += part[((size_t)c * kSobSlots + k) * nE + I];
-    s[k] = v;
-  }
+  sum_chunks4<kSobSlots>(part, nc, -1, kSobSlots, nE, I, valid, s);
+  if (threadIdx.x >= 64 || !valid) return;
   int2 e = edges[I];
   double a[3], b[3];
   for (int k = 0; k < 3; ++k) {
@@ -912,7 +936,7 @@ rc_status launch_tpe(const Curve& c, double alpha, double beta, rc_dtype prec, b
   }
   RC_HIP(hipGetLastError());
   const int band_chunk = (prec == RC_F32 && c.chain) ? c.nchunk : -1;
-  hipLaunchKernelGGL(k_tpe_finalize, dim3(cdiv(c.nE, 256)), dim3(256), 0, s, c.part, c.nchunk,
+  hipLaunchKernelGGL(k_tpe_finalize, dim3(cdiv(c.nE, 64)), dim3(256), 0, s, c.part, c.nchunk,
                      (const int*)(c.n_inst > 0 ? c.nch_e : nullptr), band_chunk, c.nE, grad ? 1 : 0,
                      (const double*)c.gd.a, (const double*)c.gd.t, c.edge_out);
   if (c.obstacle.on) {
@@ -969,7 +993,7 @@ rc_status launch_sobolev(const Curve& c, double alpha, double beta, rc_dtype pre
   }
   RC_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_edge_length<double>, g1, b1, 0, s, c.gd.a, c.nE, c.edge_out);
-  hipLaunchKernelGGL(k_sob_finalize, g1, b1, 0, s, c.part, c.nchunk,
+  hipLaunchKernelGGL(k_sob_finalize, dim3(cdiv(c.nE, 64)), dim3(256), 0, s, c.part, c.nchunk,
                      (const int*)(c.n_inst > 0 ? c.nch_e : nullptr), c.nE, X, c.edges, c.edge_out);
   hipLaunchKernelGGL(k_gather_sob, dim3(cdiv(c.nV, 256)), b1, 0, s, c.edge_out, c.inc_off, c.inc, c.nV, Y,
                      diag);
