@@ -244,57 +244,65 @@ __global__ __launch_bounds__(kTile) void k_tpe_items(
 
 // FP64 near band: for target I, every source J of the same chain at most
 // kBand apart (the pairs the BAND pair kernel skips), with the exact
-// shared-vertex exclusion.  Writes the partial-sum chunk `chunk`.
+// shared-vertex exclusion.  Four lanes share a target's band (lane j takes the
+// positions q0 + j, q0 + j + 4, ...) and their sums are added across the lanes
+// in a fixed order.  Writes the partial-sum chunk `chunk`.
 template <int EC, bool GRAD>
-__global__ void k_tpe_band(const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB,
-                           const V4<double>* __restrict__ GT, const int2* __restrict__ edges,
-                           const int4* __restrict__ cinfo, const int* __restrict__ chain_edge, int nE,
-                           double half_alpha, double half_beta, double beta, int chunk, const int* __restrict__ inst_of_edge,
-                           const int* __restrict__ mask, double* __restrict__ part) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nE) return;
-  if (mask && !mask[inst_of_edge[I]]) return;
-  const V4<double> a = GA[I], b = GB[I], t = GT[I];
-  const int2 ei = edges[I];
-  const int4 ci = cinfo[I];
-  const int m = ci.z;
-  int q0, q1;
-  if (ci.w && m <= 2 * kBand + 1) {
-    q0 = 0;
-    q1 = m - 1;
-  } else if (ci.w) {
-    q0 = ci.y - kBand;
-    q1 = ci.y + kBand;
-  } else {
-    q0 = max(0, ci.y - kBand);
-    q1 = min(m - 1, ci.y + kBand);
-  }
+__global__ __launch_bounds__(256) void k_tpe_band(const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB,
+                                                  const V4<double>* __restrict__ GT, const int2* __restrict__ edges,
+                                                  const int4* __restrict__ cinfo, const int* __restrict__ chain_edge,
+                                                  int nE, double half_alpha, double half_beta, double beta, int chunk,
+                                                  const int* __restrict__ inst_of_edge, const int* __restrict__ mask,
+                                                  double* __restrict__ part) {
+  const int tg = blockIdx.x * blockDim.x + threadIdx.x;
+  const int I = tg / 4, sub = tg % 4;
+  bool valid = I < nE;
+  if (valid && mask) valid = mask[inst_of_edge[I]] != 0;
   double E = 0, S = 0, G1x = 0, G1y = 0, G1z = 0, G2x = 0, G2y = 0, G2z = 0;
-  double Gt1 = 0, Gt2 = 0, Hx = 0, Hy = 0, Hz = 0, Ht = 0;
-  for (int q = q0; q <= q1; ++q) {
-    const int qq = ((q % m) + m) % m;
-    const int J = chain_edge[ci.x + qq];
-    const int2 ej = edges[J];
-    const bool s11 = ei.x == ej.x, s12 = ei.x == ej.y, s21 = ei.y == ej.x, s22 = ei.y == ej.y;
-    if (s11 | s12 | s21 | s22) continue;
-    const V4<double> qa = GA[J], qb = GB[J], qt = GT[J];
-    const double w = 0.25 * qa.w;
-    tpe_vertex_pair<double, EC, GRAD>(a.x, a.y, a.z, t.x, t.y, t.z, qa.x, qa.y, qa.z, qt.x, qt.y, qt.z, false, w,
-                                      half_alpha, half_beta, beta, E, S, G1x, G1y, G1z, Gt1, Hx, Hy, Hz, Ht);
-    tpe_vertex_pair<double, EC, GRAD>(a.x, a.y, a.z, t.x, t.y, t.z, qb.x, qb.y, qb.z, qt.x, qt.y, qt.z, false, w,
-                                      half_alpha, half_beta, beta, E, S, G1x, G1y, G1z, Gt1, Hx, Hy, Hz, Ht);
-    tpe_vertex_pair<double, EC, GRAD>(b.x, b.y, b.z, t.x, t.y, t.z, qa.x, qa.y, qa.z, qt.x, qt.y, qt.z, false, w,
-                                      half_alpha, half_beta, beta, E, S, G2x, G2y, G2z, Gt2, Hx, Hy, Hz, Ht);
-    tpe_vertex_pair<double, EC, GRAD>(b.x, b.y, b.z, t.x, t.y, t.z, qb.x, qb.y, qb.z, qt.x, qt.y, qt.z, false, w,
-                                      half_alpha, half_beta, beta, E, S, G2x, G2y, G2z, Gt2, Hx, Hy, Hz, Ht);
+  double Gt1 = 0, Gt2 = 0, Hx = 0, Hy = 0, Hz = 0;
+  V4<double> t{0, 0, 0, 0};
+  if (valid) {
+    const V4<double> a = GA[I], b = GB[I];
+    t = GT[I];
+    const int2 ei = edges[I];
+    const int4 ci = cinfo[I];
+    const int m = ci.z;
+    int q0, q1;
+    if (ci.w && m <= 2 * kBand + 1) {
+      q0 = 0;
+      q1 = m - 1;
+    } else if (ci.w) {
+      q0 = ci.y - kBand;
+      q1 = ci.y + kBand;
+    } else {
+      q0 = max(0, ci.y - kBand);
+      q1 = min(m - 1, ci.y + kBand);
+    }
+    for (int q = q0 + sub; q <= q1; q += 4) {
+      const int qq = ((q % m) + m) % m;
+      const int J = chain_edge[ci.x + qq];
+      const int2 ej = edges[J];
+      const bool skip = (ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y);
+      const V4<double> qa = GA[J], qb = GB[J], qt = GT[J];
+      tpe_edge_pair<double, EC, GRAD, true>(a.x, a.y, a.z, b.x, b.y, b.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z, qb.x,
+                                            qb.y, qb.z, qt.x, qt.y, qt.z, qa.w, skip ? 0.0 : 0.25 * qa.w,
+                                            skip ? 1.0 : 0.0, half_alpha, half_beta, beta, E, S, G1x, G1y, G1z, Gt1,
+                                            G2x, G2y, G2z, Gt2, Hx, Hy, Hz);
+    }
   }
+  auto red4 = [](double v) {  // (v0 + v1) + (v2 + v3) on every lane of the group
+    v += __shfl_xor(v, 1, 64);
+    return v + __shfl_xor(v, 2, 64);
+  };
   constexpr int NS = GRAD ? kTpeSlots : 1;
+  double v[kTpeSlots] = {E, S, G1x, G1y, G1z, G2x, G2y, G2z, Gt1, Gt2, Hx, Hy, Hz, 0.0};
+#pragma unroll
+  for (int k = 0; k < NS; ++k) v[k] = red4(v[k]);
+  if (GRAD) v[13] = t.x * v[10] + t.y * v[11] + t.z * v[12];  // T.H: H holds multiples of T
+  if (!valid || sub != 0) return;
   double* out = part + (size_t)chunk * NS * nE + I;
-  out[0] = E;
-  if constexpr (GRAD) {
-    const double v[kTpeSlots] = {E, S, G1x, G1y, G1z, G2x, G2y, G2z, Gt1, Gt2, Hx, Hy, Hz, Ht};
-    for (int k = 1; k < kTpeSlots; ++k) out[(size_t)k * nE] = v[k];
-  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) out[(size_t)k * nE] = v[k];
 }
 
 // Sums over the partial-sum chunks of ns <= NS slots for the 64 edges of a
@@ -894,7 +902,7 @@ static void run_tpe(const Curve& c, const EdgeGeom<R>& g, double alpha, double b
                          R(0.5 * alpha), R(0.5 * beta), R(beta), c.part);
     if (timed) c.timer->mark(c.timer->tpe, s);
     if (band)
-      hipLaunchKernelGGL((k_tpe_band<EC, GRAD>), dim3(cdiv(c.nE, 64)), dim3(64), 0, s, c.gd.a, c.gd.b, c.gd.t,
+      hipLaunchKernelGGL((k_tpe_band<EC, GRAD>), dim3(cdiv(c.nE, 64)), dim3(256), 0, s, c.gd.a, c.gd.b, c.gd.t,
                          c.edges, c.cinfo, c.chain_edge, c.nE, 0.5 * alpha, 0.5 * beta, beta, c.nchunk, c.inst_of_edge,
                          c.inst_mask, c.part);
     return;
@@ -904,7 +912,7 @@ static void run_tpe(const Curve& c, const EdgeGeom<R>& g, double alpha, double b
     hipLaunchKernelGGL((k_tpe_pairs<R, EC, GRAD, true>), grid, dim3(kTile), 0, s, g.a, g.b, g.t, c.edges, c.cinfo,
                        c.nE, c.src_per_chunk, R(0.5 * alpha), R(0.5 * beta), R(beta), c.part);
     if (timed) c.timer->mark(c.timer->tpe, s);
-    hipLaunchKernelGGL((k_tpe_band<EC, GRAD>), dim3(cdiv(c.nE, 64)), dim3(64), 0, s, c.gd.a, c.gd.b, c.gd.t,
+    hipLaunchKernelGGL((k_tpe_band<EC, GRAD>), dim3(cdiv(c.nE, 64)), dim3(256), 0, s, c.gd.a, c.gd.b, c.gd.t,
                        c.edges, c.cinfo, c.chain_edge, c.nE, 0.5 * alpha, 0.5 * beta, beta, c.nchunk, c.inst_of_edge,
                          c.inst_mask, c.part);
   } else {

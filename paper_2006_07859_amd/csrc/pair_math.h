@@ -99,6 +99,29 @@ __device__ __forceinline__ void sob_powers(R r2, R half_expo, R& ri, R& p) {
   }
 }
 
+// ri = r2^-1 and rb = r2^(-beta/2) for one vertex pair of the energy.  In
+// FP64 with beta = 4.5 both are powers of q = r2^(-1/4) (ri = q^4, rb = q^9),
+// with q from an FP32 estimate and two Newton steps as in sob_powers.
+template <int EC, typename R>
+__device__ __forceinline__ void tpe_powers(R r2, R half_beta, R& ri, R& rb) {
+  if constexpr (EC == kA2B45 && std::is_same<R, double>::value) {
+    double q = (double)__builtin_amdgcn_sqrtf(__builtin_amdgcn_rsqf((float)r2));
+    const double mr = -0.25 * r2;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const double q2 = q * q;
+      q = fma(q, fma(mr, q2 * q2, 0.25), q);
+    }
+    const double q2 = q * q;
+    ri = q2 * q2;
+    rb = ri * ri * q;
+  } else {
+    const R rs = f_rsq<R>(r2);
+    ri = rs * rs;
+    rb = pow_beta<EC, R>(r2, rs, ri, half_beta);
+  }
+}
+
 template <typename R>
 __device__ __forceinline__ R cross_norm2(R tx, R ty, R tz, R dx, R dy, R dz) {
   // |T x d|^2 from the cross product itself: accurate when d is nearly
@@ -201,12 +224,15 @@ __device__ __forceinline__ void tpe_edge_pair(
   const R t21 = t11 + lI, t22 = t12 + lI;
   const R r11 = t11 * t11 + cI1, r12 = t12 * t12 + cI2;
   const R r21 = t21 * t21 + cI1, r22 = t22 * t22 + cI2;
-  const R rs11 = f_rsq<R>(r11), rs12 = f_rsq<R>(r12), rs21 = f_rsq<R>(r21), rs22 = f_rsq<R>(r22);
-  const R ri11 = rs11 * rs11, ri12 = rs12 * rs12, ri21 = rs21 * rs21, ri22 = rs22 * rs22;
-  const R rb11 = pow_beta<EC, R>(r11, rs11, ri11, half_beta) * w;
-  const R rb12 = pow_beta<EC, R>(r12, rs12, ri12, half_beta) * w;
-  const R rb21 = pow_beta<EC, R>(r21, rs21, ri21, half_beta) * w;
-  const R rb22 = pow_beta<EC, R>(r22, rs22, ri22, half_beta) * w;
+  R ri11, ri12, ri21, ri22, rb11, rb12, rb21, rb22;
+  tpe_powers<EC, R>(r11, half_beta, ri11, rb11);
+  tpe_powers<EC, R>(r12, half_beta, ri12, rb12);
+  tpe_powers<EC, R>(r21, half_beta, ri21, rb21);
+  tpe_powers<EC, R>(r22, half_beta, ri22, rb22);
+  rb11 *= w;
+  rb12 *= w;
+  rb21 *= w;
+  rb22 *= w;
   R caI1, fI1, caI2, fI2;
   pow_alpha<EC, R>(cI1, half_alpha, caI1, fI1);
   pow_alpha<EC, R>(cI2, half_alpha, caI2, fI2);
