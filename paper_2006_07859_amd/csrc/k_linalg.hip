@@ -88,24 +88,71 @@ int dot_scratch_size(int m) { return kRedBlocks * m; }
 // ---------------------------------------------------------------------------
 // C[m x n] = op(A) op(B) + beta C, row-major; op(A) is m x k (A stored k x m
 // when transA), op(B) is k x n (B stored n x k when transB).
-__global__ void k_gemm(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C, int m,
-                       int n, int k, double beta, int transA, int transB) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  int i = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= m || j >= n) return;
-  double s = 0.0;
-  for (int p = 0; p < k; ++p) {
-    const double av = transA ? A[(size_t)p * m + i] : A[(size_t)i * k + p];
-    const double bv = transB ? B[(size_t)j * k + p] : B[(size_t)p * n + j];
-    s += av * bv;
+// C = op(A) op(B) (+ beta C), row major, op = transpose when the flag is set:
+// 64 x 64 tiles of C per workgroup of 256 threads, each thread 4 x 4 entries
+// (rows ty + 16 i, columns tx + 16 j), k staged through LDS 16 at a time;
+// out-of-range rows, columns and k are zero-filled.
+constexpr int kGemmT = 64, kGemmK = 16;
+
+__global__ __launch_bounds__(256) void k_gemm(const double* __restrict__ A, const double* __restrict__ B,
+                                              double* __restrict__ C, int m, int n, int k, double beta, int transA,
+                                              int transB) {
+  __shared__ double As[kGemmK][kGemmT + 1], Bs[kGemmK][kGemmT + 1];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int i0 = blockIdx.y * kGemmT, j0 = blockIdx.x * kGemmT;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int p0 = 0; p0 < k; p0 += kGemmK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // 64 x 16 of op(A) and 16 x 64 of op(B), four entries per thread
+      const int e = threadIdx.x + 256 * q;
+      {
+        // op(A)(i, p): consecutive threads along p when A is row major, along i when transposed
+        const int ii = transA ? e % kGemmT : e / kGemmK, pp = transA ? e / kGemmT : e % kGemmK;
+        const int i = i0 + ii, p = p0 + pp;
+        As[pp][ii] = (i < m && p < k) ? (transA ? A[(size_t)p * m + i] : A[(size_t)i * k + p]) : 0.0;
+      }
+      {
+        // op(B)(p, j): consecutive threads along j when B is row major, along p when transposed
+        const int jj = transB ? e / kGemmK : e % kGemmT, pp = transB ? e % kGemmK : e / kGemmT;
+        const int j = j0 + jj, p = p0 + pp;
+        Bs[pp][jj] = (j < n && p < k) ? (transB ? B[(size_t)j * k + p] : B[(size_t)p * n + j]) : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kGemmK; ++p) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[p][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[p][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
   }
-  C[(size_t)i * n + j] = s + (beta != 0.0 ? beta * C[(size_t)i * n + j] : 0.0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = i0 + ty + 16 * i, c = j0 + tx + 16 * j;
+      if (r < m && c < n) {
+        const size_t idx = (size_t)r * n + c;
+        C[idx] = acc[i][j] + (beta != 0.0 ? beta * C[idx] : 0.0);
+      }
+    }
 }
 
 void dense_gemm(const double* A, const double* B, double* C, int m, int n, int k, double beta, bool transA,
                 hipStream_t s, bool transB) {
-  dim3 b(16, 16), g(cdiv(n, 16), cdiv(m, 16));
-  hipLaunchKernelGGL(k_gemm, g, b, 0, s, A, B, C, m, n, k, beta, transA ? 1 : 0, transB ? 1 : 0);
+  dim3 g(cdiv(n, kGemmT), cdiv(m, kGemmT));
+  hipLaunchKernelGGL(k_gemm, g, dim3(256), 0, s, A, B, C, m, n, k, beta, transA ? 1 : 0, transB ? 1 : 0);
 }
 
 // y = A x for a dense n x n row-major A and a vector x (one wave per row).
