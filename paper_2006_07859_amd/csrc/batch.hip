@@ -399,22 +399,27 @@ constexpr int kGT = 32;
 
 // Scalar Gauss-Jordan of a diagonal tile in LDS (rows and columns >= kk hold
 // the identity), by a workgroup of 256 threads; info is raised when a pivot is
-// not positive.  Begins and ends with the tile visible to the whole workgroup.
-__device__ __forceinline__ void gj_tile_invert(double (&D)[kGT][kGT + 1], double (&f)[kGT], int kk, int* info) {
+// not positive.  Pivot p maps the tile from one buffer to the other (the new
+// entries depend only on the old pivot row, pivot column and entry), so each
+// pivot takes one barrier; with kGT even the inverse ends in D.  Begins and
+// ends with the tile visible to the whole workgroup.
+__device__ __forceinline__ void gj_tile_invert(double (&D)[kGT][kGT + 1], double (&D2)[kGT][kGT + 1], int kk,
+                                               int* info) {
+  static_assert(kGT % 2 == 0, "the inverse ends in D");
   const int tid = threadIdx.x;
   for (int p = 0; p < kGT; ++p) {
-    if (info && tid == 0 && p < kk && !(D[p][p] > 0.0)) atomicMax(info, 1);  // not positive definite
-    const double ip = 1.0 / D[p][p];
-    __syncthreads();
-    if (tid < kGT) {
-      f[tid] = tid == p ? 0.0 : D[tid][p];
-      D[p][tid] = (tid == p ? 1.0 : D[p][tid]) * ip;
-    }
-    __syncthreads();
+    double (&src)[kGT][kGT + 1] = (p % 2 == 0) ? D : D2;
+    double (&dst)[kGT][kGT + 1] = (p % 2 == 0) ? D2 : D;
+    const double piv = src[p][p];
+    if (info && tid == 0 && p < kk && !(piv > 0.0)) atomicMax(info, 1);  // not positive definite
+    const double ip = 1.0 / piv;
     for (int e = tid; e < kGT * kGT; e += 256) {
       const int r = e / kGT, c = e % kGT;
-      if (r == p) continue;
-      D[r][c] = (c == p) ? -f[r] * D[p][p] : D[r][c] - f[r] * D[p][c];
+      double v;
+      if (r == p) v = (c == p ? 1.0 : src[p][c]) * ip;
+      else if (c == p) v = -src[r][p] * ip;
+      else v = src[r][c] - src[r][p] * (src[p][c] * ip);
+      dst[r][c] = v;
     }
     __syncthreads();
   }
@@ -425,7 +430,7 @@ __global__ __launch_bounds__(256) void k_gj_panel(int k, const int* __restrict__
                                                   const long long* __restrict__ blk_off, double* __restrict__ Minv,
                                                   double* __restrict__ S, int* __restrict__ info) {
   __shared__ double D[kGT][kGT + 1];
-  __shared__ double f[kGT];
+  __shared__ double D2[kGT][kGT + 1];  // second buffer of the tile inversion
   const int q = list[blockIdx.x];
   const int m = chain_voff[q + 1] - chain_voff[q];
   double* M = Minv + blk_off[q];
@@ -442,7 +447,7 @@ __global__ __launch_bounds__(256) void k_gj_panel(int k, const int* __restrict__
     Sq[e] = c < kk ? M[(size_t)i * m + r0 + c] : 0.0;
   }
   __syncthreads();
-  gj_tile_invert(D, f, kk, info);
+  gj_tile_invert(D, D2, kk, info);
   // row panel: A_kj <- Dinv A_kj for the columns outside tile k
   for (int c = tid; c < m; c += 256) {
     if (c >= r0 && c < r0 + kk) continue;
@@ -515,14 +520,14 @@ __global__ __launch_bounds__(256) void k_gj_update(int k, const int* __restrict_
 __global__ __launch_bounds__(256) void k_gj_diag(int k, const double* __restrict__ M, int m,
                                                  double* __restrict__ dinv, int* __restrict__ info) {
   __shared__ double D[kGT][kGT + 1];
-  __shared__ double f[kGT];
+  __shared__ double D2[kGT][kGT + 1];  // second buffer of the tile inversion
   const int r0 = k * kGT, kk = min(kGT, m - r0);
   for (int e = threadIdx.x; e < kGT * kGT; e += 256) {
     const int r = e / kGT, c = e % kGT;
     D[r][c] = (r < kk && c < kk) ? M[(size_t)(r0 + r) * m + r0 + c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  gj_tile_invert(D, f, kk, info);
+  gj_tile_invert(D, D2, kk, info);
   for (int e = threadIdx.x; e < kGT * kGT; e += 256) dinv[e] = D[e / kGT][e % kGT];
 }
 
