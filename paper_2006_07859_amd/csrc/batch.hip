@@ -513,10 +513,11 @@ __global__ __launch_bounds__(256) void k_gj_update(int k, const int* __restrict_
 
 // The panel step of one large matrix over many workgroups: k_gj_diag inverts
 // the diagonal tile (one workgroup) into dinv [kGT][kGT]; k_gj_rowcol saves
-// the old column panel of rows [256 b, 256 b + 256) and forms the row panel
-// of columns [256 b, 256 b + 256) in workgroup b; the workgroup whose rows hold
-// the diagonal tile writes its inverse after saving those rows, so no
-// workgroup reads a tile another one writes.
+// the old column panel of rows [64 b, 64 b + 64) and forms the row panel of
+// columns [64 b, 64 b + 64) in workgroup b (four threads per column, eight
+// rows each); the workgroup whose rows hold the diagonal tile writes its
+// inverse after saving those rows, so no workgroup reads a tile another one
+// writes.
 __global__ __launch_bounds__(256) void k_gj_diag(int k, const double* __restrict__ M, int m,
                                                  double* __restrict__ dinv, int* __restrict__ info) {
   __shared__ double D[kGT][kGT + 1];
@@ -537,24 +538,25 @@ __global__ __launch_bounds__(256) void k_gj_rowcol(int k, double* __restrict__ M
   const int tid = threadIdx.x, b = blockIdx.x;
   const int r0 = k * kGT, kk = min(kGT, m - r0);
   for (int e = tid; e < kGT * kGT; e += 256) D[e / kGT][e % kGT] = dinv[e];
-  for (int e = tid; e < 256 * kGT; e += 256) {  // the old column panel
-    const int i = b * 256 + e / kGT, c = e % kGT;
+  for (int e = tid; e < 64 * kGT; e += 256) {  // the old column panel
+    const int i = b * 64 + e / kGT, c = e % kGT;
     if (i < m) S[(size_t)i * kGT + c] = c < kk ? M[(size_t)i * m + r0 + c] : 0.0;
   }
   __syncthreads();
-  const int c = b * 256 + tid;  // row panel: A_kj <- Dinv A_kj for the columns outside tile k
-  if (c < m && !(c >= r0 && c < r0 + kk)) {
-    double col[kGT];
+  const int c = b * 64 + tid % 64, rq = tid / 64;  // row panel: A_kj <- Dinv A_kj outside tile k
+  const bool cact = c < m && !(c >= r0 && c < r0 + kk);
+  double col[kGT];
 #pragma unroll
-    for (int s2 = 0; s2 < kGT; ++s2) col[s2] = s2 < kk ? M[(size_t)(r0 + s2) * m + c] : 0.0;
-    for (int r = 0; r < kk; ++r) {
+  for (int s2 = 0; s2 < kGT; ++s2) col[s2] = (cact && s2 < kk) ? M[(size_t)(r0 + s2) * m + c] : 0.0;
+  __syncthreads();  // the four threads of a column have read it before any of them writes it
+  if (cact)
+    for (int r = rq * (kGT / 4); r < min(kk, (rq + 1) * (kGT / 4)); ++r) {
       double a = 0.0;
 #pragma unroll
       for (int s2 = 0; s2 < kGT; ++s2) a += D[r][s2] * col[s2];
       M[(size_t)(r0 + r) * m + c] = a;
     }
-  }
-  if (r0 / 256 == b)  // the diagonal tile, after this workgroup saved its rows
+  if (r0 / 64 == b)  // the diagonal tile, after this workgroup saved its rows
     for (int e = tid; e < kk * kk; e += 256) {
       const int r = e / kk, cc = e % kk;
       M[(size_t)(r0 + r) * m + r0 + cc] = D[r][cc];
@@ -579,7 +581,7 @@ void gj_invert_spd(double* M, int m, int* meta, long long* off, double* col, int
   double* dinv = col + (size_t)kGT * m;
   for (int k = 0; k < nb; ++k) {
     hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, s, k, (const double*)M, m, dinv, info);
-    hipLaunchKernelGGL(k_gj_rowcol, dim3(cdiv(m, 256)), dim3(256), 0, s, k, M, m, (const double*)dinv, col);
+    hipLaunchKernelGGL(k_gj_rowcol, dim3(cdiv(m, 64)), dim3(256), 0, s, k, M, m, (const double*)dinv, col);
     hipLaunchKernelGGL(k_gj_update, dim3(nb * nb), dim3(256), 0, s, k, (const int*)meta, (const int*)(meta + 3), 1,
                        (const int*)(meta + 1), (const long long*)off, M, (const double*)col);
   }
