@@ -33,11 +33,11 @@ sys.path.insert(0, ROOT)
 # the transcendental operations (rsqrt, sqrt) are counted separately and not
 # included.  Energy + differential: 280 flops for the gather form whose four
 # vertex pairs share the difference vectors, |T x d|, T.d and r^-beta work (the
-# lower end of its 280-300 estimate).  The (2, 4.5) kernel executes 214 flops
+# lower end of its 280-300 estimate).  The (2, 4.5) kernel executes 213 flops
 # and 8 transcendentals per pair (its gfx950 inner loop), reported beside it;
 # evaluating the four vertex pairs independently would take 344.
 FLOPS_PER_PAIR_TPE = 280   # energy + differential, algorithmic
-FLOPS_PER_PAIR_TPE_EXEC = 214  # energy + differential, executed by the (2, 4.5) FP32 kernel
+FLOPS_PER_PAIR_TPE_EXEC = 213  # energy + differential, executed by the (2, 4.5) FP32 kernel
 # Operator A = B + B0 applied to 3 right-hand sides: about 100 flops per pair for
 # the gather form; the FP32 kernel executes 144 and 8 transcendentals per pair, the
 # FP64 one 196 with its powers from an FP32 estimate and Newton steps.

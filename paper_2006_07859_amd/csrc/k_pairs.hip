@@ -172,15 +172,13 @@ __device__ __forceinline__ void tpe_tile(const V4<R>* __restrict__ GA, const V4<
               skip = (ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y);
             }
             const R w = skip ? R(0) : qb.w;  // l_J / 4, staged in the free slot
-            tpe_edge_pair<R, EC, GRAD, true>(a.x, a.y, a.z, b.x, b.y, b.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z,
-                                             qb.x, qb.y, qb.z, qt.x, qt.y, qt.z, qa.w, w, skip ? R(1) : R(0),
-                                             half_alpha, half_beta, beta, E, S, G1x, G1y, G1z, Gt1, G2x, G2y,
-                                             G2z, Gt2, Hx, Hy, Hz);
+            tpe_edge_pair<R, EC, GRAD, true>(a.x, a.y, a.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z, qt.x, qt.y, qt.z,
+                                             qa.w, w, skip ? R(1) : R(0), half_alpha, half_beta, beta, E, S, G1x,
+                                             G1y, G1z, Gt1, G2x, G2y, G2z, Gt2, Hx, Hy, Hz);
           } else {
-            tpe_edge_pair<R, EC, GRAD, false>(a.x, a.y, a.z, b.x, b.y, b.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z,
-                                              qb.x, qb.y, qb.z, qt.x, qt.y, qt.z, qa.w, qb.w, R(0), half_alpha,
-                                              half_beta, beta, E, S, G1x, G1y, G1z, Gt1, G2x, G2y, G2z, Gt2, Hx,
-                                              Hy, Hz);
+            tpe_edge_pair<R, EC, GRAD, false>(a.x, a.y, a.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z, qt.x, qt.y,
+                                              qt.z, qa.w, qb.w, R(0), half_alpha, half_beta, beta, E, S, G1x, G1y,
+                                              G1z, Gt1, G2x, G2y, G2z, Gt2, Hx, Hy, Hz);
           }
         }
       };
@@ -284,10 +282,9 @@ __global__ __launch_bounds__(256) void k_tpe_band(const V4<double>* __restrict__
       const int2 ej = edges[J];
       const bool skip = (ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y);
       const V4<double> qa = GA[J], qb = GB[J], qt = GT[J];
-      tpe_edge_pair<double, EC, GRAD, true>(a.x, a.y, a.z, b.x, b.y, b.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z, qb.x,
-                                            qb.y, qb.z, qt.x, qt.y, qt.z, qa.w, skip ? 0.0 : 0.25 * qa.w,
-                                            skip ? 1.0 : 0.0, half_alpha, half_beta, beta, E, S, G1x, G1y, G1z, Gt1,
-                                            G2x, G2y, G2z, Gt2, Hx, Hy, Hz);
+      tpe_edge_pair<double, EC, GRAD, true>(a.x, a.y, a.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z, qt.x, qt.y, qt.z,
+                                            qa.w, skip ? 0.0 : 0.25 * qa.w, skip ? 1.0 : 0.0, half_alpha, half_beta,
+                                            beta, E, S, G1x, G1y, G1z, Gt1, G2x, G2y, G2z, Gt2, Hx, Hy, Hz);
     }
   }
   auto red4 = [](double v) {  // (v0 + v1) + (v2 + v3) on every lane of the group

@@ -192,14 +192,16 @@ __device__ __forceinline__ void tpe_vertex_pair(
 // all-pairs kernels, with the work the pairs share done once.  Target I has
 // endpoints a (i1) and b (i2) and unit tangent T, source J endpoints c (j1)
 // and e (j2) and unit tangent U; l_I and l_J are their lengths, so that
-// b = a + l_I T and e = c + l_J U.  Hence, with d(p, q) = p - q:
-//  * |T x d(p, q)| does not depend on p, and |U x d(p, q)| not on q: two cross
-//    products of each kind instead of four;
-//  * T.d(b, q) = T.d(a, q) + l_I and U.d(p, e) = U.d(p, c) - l_J;
+// b = a + l_I T and e = c + l_J U.  Hence, with d(p, q) = p - q and d = d(a, c):
+//  * |T x d(p, q)| does not depend on p, and |U x d(p, q)| not on q, with
+//    T x d(a, e) = T x d - l_J (T x U) and U x d(b, c) = U x d - l_I (T x U);
+//  * T.d(a, e) = T.d - l_J (T.U), T.d(b, q) = T.d(a, q) + l_I, and likewise
+//    U.d(b, c) = U.d + l_I (T.U), U.d(p, e) = U.d(p, c) - l_J;
 //  * |d|^2 = |T x d|^2 + (T.d)^2 (|T| = 1), a sum of two non-negative terms;
-//  * the gradient sums at p use d(p, e) = d(p, c) - l_J U, and the sum H,
-//    which the caller projects onto the plane normal to T, is accumulated
-//    modulo multiples of T with d(b, q) = d(a, q) + l_I T.
+//  * the gradient sums use d(p, e) = d(p, c) - l_J U and d(b, c) = d + l_I T,
+//    whose T part joins the T coefficient Gt2; the sum H, which the caller
+//    projects onto the plane normal to T, is accumulated modulo multiples of
+//    T (d(b, q) = d(a, q) + l_I T).
 // Every identity holds exactly for the real geometry; in rounded arithmetic
 // the terms differ from the direct ones by the rounding of the coordinates.
 // w = l_J / 4, and 0 for a skipped pair, whose skipv = 1 keeps |d|^2 >= 1
@@ -207,20 +209,22 @@ __device__ __forceinline__ void tpe_vertex_pair(
 // T.H replaces it after the sum.
 template <typename R, int EC, bool GRAD, bool SKIP>
 __device__ __forceinline__ void tpe_edge_pair(
-    R ax, R ay, R az, R bx, R by, R bz, R Tx, R Ty, R Tz, R lI,
-    R cx, R cy, R cz, R ex, R ey, R ez, R Ux, R Uy, R Uz, R lJ,
+    R ax, R ay, R az, R Tx, R Ty, R Tz, R lI, R cx, R cy, R cz, R Ux, R Uy, R Uz, R lJ,
     R w, R skipv, R half_alpha, R half_beta, R beta,
     R& E, R& S, R& G1x, R& G1y, R& G1z, R& Gt1, R& G2x, R& G2y, R& G2z, R& Gt2, R& Hx, R& Hy, R& Hz) {
-  const R d11x = ax - cx, d11y = ay - cy, d11z = az - cz;  // d(a, c)
-  const R d12x = ax - ex, d12y = ay - ey, d12z = az - ez;  // d(a, e)
-  R cI1 = cross_norm2<R>(Tx, Ty, Tz, d11x, d11y, d11z);
-  R cI2 = cross_norm2<R>(Tx, Ty, Tz, d12x, d12y, d12z);
+  const R dx = ax - cx, dy = ay - cy, dz = az - cz;  // d(a, c)
+  const R wx = Ty * Uz - Tz * Uy, wy = Tz * Ux - Tx * Uz, wz = Tx * Uy - Ty * Ux;  // T x U
+  const R tu = Tx * Ux + Ty * Uy + Tz * Uz;
+  const R xIx = Ty * dz - Tz * dy, xIy = Tz * dx - Tx * dz, xIz = Tx * dy - Ty * dx;  // T x d(a, c)
+  const R yIx = xIx - lJ * wx, yIy = xIy - lJ * wy, yIz = xIz - lJ * wz;                // T x d(a, e)
+  R cI1 = xIx * xIx + xIy * xIy + xIz * xIz;
+  R cI2 = yIx * yIx + yIy * yIy + yIz * yIz;
   if constexpr (SKIP) {
     cI1 += skipv;
     cI2 += skipv;
   }
-  const R t11 = Tx * d11x + Ty * d11y + Tz * d11z;
-  const R t12 = Tx * d12x + Ty * d12y + Tz * d12z;
+  const R t11 = Tx * dx + Ty * dy + Tz * dz;
+  const R t12 = t11 - lJ * tu;
   const R t21 = t11 + lI, t22 = t12 + lI;
   const R r11 = t11 * t11 + cI1, r12 = t12 * t12 + cI2;
   const R r21 = t21 * t21 + cI1, r22 = t22 * t22 + cI2;
@@ -239,14 +243,15 @@ __device__ __forceinline__ void tpe_edge_pair(
   E = fma(caI1, rb11 + rb21, E);
   E = fma(caI2, rb12 + rb22, E);
   if constexpr (GRAD) {
-    const R d21x = bx - cx, d21y = by - cy, d21z = bz - cz;  // d(b, c)
-    const R cJ1 = cross_norm2<R>(Ux, Uy, Uz, d11x, d11y, d11z);
-    const R cJ2 = cross_norm2<R>(Ux, Uy, Uz, d21x, d21y, d21z);
+    const R xJx = Uy * dz - Uz * dy, xJy = Uz * dx - Ux * dz, xJz = Ux * dy - Uy * dx;  // U x d(a, c)
+    const R yJx = xJx - lI * wx, yJy = xJy - lI * wy, yJz = xJz - lI * wz;                // U x d(b, c)
+    const R cJ1 = xJx * xJx + xJy * xJy + xJz * xJz;
+    const R cJ2 = yJx * yJx + yJy * yJy + yJz * yJz;
     R caJ1, fJ1, caJ2, fJ2;
     pow_alpha<EC, R>(cJ1, half_alpha, caJ1, fJ1);
     pow_alpha<EC, R>(cJ2, half_alpha, caJ2, fJ2);
-    const R u11 = Ux * d11x + Uy * d11y + Uz * d11z;
-    const R u21 = Ux * d21x + Uy * d21y + Uz * d21z;
+    const R u11 = Ux * dx + Uy * dy + Uz * dz;
+    const R u21 = u11 + lI * tu;
     const R u12 = u11 - lJ, u22 = u21 - lJ;
     // k(d, T) + k(d, U) per vertex pair, and its sum
     const R s11 = caI1 + caJ1, s12 = caI2 + caJ1, s21 = caI1 + caJ2, s22 = caI2 + caJ2;
@@ -259,23 +264,25 @@ __device__ __forceinline__ void tpe_edge_pair(
     const R c12 = rb12 * (R(2) * (fI2 + fJ1) - beta * s12 * ri12);
     const R c21 = rb21 * (R(2) * (fI1 + fJ2) - beta * s21 * ri21);
     const R c22 = rb22 * (R(2) * (fI2 + fJ2) - beta * s22 * ri22);
-    // G at p: sum over q of c d(p, q) - 2 fJ rb (U.d) U, with d(p, e) = d(p, c) - l_J U
+    // G at p: sum over q of c d(p, q) - 2 fJ rb (U.d) U, with d(p, e) = d(p, c) - l_J U;
+    // at b, d(b, c) = d + l_I T, whose T part g2 l_I goes to the T coefficient
     const R g1 = c11 + c12, h1 = R(2) * fJ1 * (rb11 * u11 + rb12 * u12) + lJ * c12;
     const R g2 = c21 + c22, h2 = R(2) * fJ2 * (rb21 * u21 + rb22 * u22) + lJ * c22;
-    G1x = fma(g1, d11x, fma(-h1, Ux, G1x));
-    G1y = fma(g1, d11y, fma(-h1, Uy, G1y));
-    G1z = fma(g1, d11z, fma(-h1, Uz, G1z));
-    G2x = fma(g2, d21x, fma(-h2, Ux, G2x));
-    G2y = fma(g2, d21y, fma(-h2, Uy, G2y));
-    G2z = fma(g2, d21z, fma(-h2, Uz, G2z));
+    G1x = fma(g1, dx, fma(-h1, Ux, G1x));
+    G1y = fma(g1, dy, fma(-h1, Uy, G1y));
+    G1z = fma(g1, dz, fma(-h1, Uz, G1z));
+    G2x = fma(g2, dx, fma(-h2, Ux, G2x));
+    G2y = fma(g2, dy, fma(-h2, Uy, G2y));
+    G2z = fma(g2, dz, fma(-h2, Uz, G2z));
     // fI rb (T.d): half the T coefficient of the gradient, and the weight of d in H
     const R k11 = fI1 * rb11 * t11, k12 = fI2 * rb12 * t12, k21 = fI1 * rb21 * t21, k22 = fI2 * rb22 * t22;
     Gt1 = fma(R(2), k11 + k12, Gt1);
-    Gt2 = fma(R(2), k21 + k22, Gt2);
-    const R m1 = k11 + k21, m2 = k12 + k22;
-    Hx = fma(m1, d11x, fma(m2, d12x, Hx));
-    Hy = fma(m1, d11y, fma(m2, d12y, Hy));
-    Hz = fma(m1, d11z, fma(m2, d12z, Hz));
+    Gt2 = fma(R(2), k21 + k22, fma(-g2, lI, Gt2));
+    // H: (k11 + k21) d + (k12 + k22) (d - l_J U)
+    const R m = (k11 + k21) + (k12 + k22), mu = lJ * (k12 + k22);
+    Hx = fma(m, dx, fma(-mu, Ux, Hx));
+    Hy = fma(m, dy, fma(-mu, Uy, Hy));
+    Hz = fma(m, dz, fma(-mu, Uz, Hz));
   }
 }
 
