@@ -39,8 +39,8 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_PAIR_TPE = 280   # energy + differential, algorithmic
 FLOPS_PER_PAIR_TPE_EXEC = 213  # energy + differential, executed by the (2, 4.5) FP32 kernel
 # Operator A = B + B0 applied to 3 right-hand sides: about 100 flops per pair for
-# the gather form; the FP32 kernel executes 144 and 8 transcendentals per pair, the
-# FP64 one 196 with its powers from an FP32 estimate and Newton steps.
+# the gather form; the FP32 kernel executes about 135 and 8 transcendentals per
+# pair, the FP64 one about 190 with its powers from an FP32 estimate and Newton steps.
 FLOPS_PER_PAIR_SOB = 100   # operator, algorithmic
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed); the non-packed issue limit is half
 PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64

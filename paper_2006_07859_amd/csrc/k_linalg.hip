@@ -1020,10 +1020,12 @@ __global__ __launch_bounds__(256) void k_apply_CT_z(const ProjData d, const doub
   if (d.pp) proj_prep_operand<256>(d, v, vert, val);
 }
 
-// The last step of k_proj_small for vertex t; val receives out_t (xacc_t when prep_x).
+// The last step of k_proj_small for vertex t; val receives out_t (xacc_t when
+// prep_x); pin and ain hold prev_t and xacc_t, loaded before the barriers.
 __device__ __forceinline__ void proj_small_vertex(const ProjData& d, int t, double* __restrict__ out,
                                                   const ProjVert& pv, double w_t, double x0, double x1, double x2,
-                                                  const double* yps, const double* ybs, double (&val)[3]) {
+                                                  const double* yps, const double* ybs, const double (&pin)[3],
+                                                  const double (&ain)[3], double (&val)[3]) {
   const int np = d.np, nV = d.nV, nb = d.nb;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
@@ -1050,11 +1052,11 @@ __device__ __forceinline__ void proj_small_vertex(const ProjData& d, int t, doub
   double o[3] = {sw * (x0 - a0), sw * (x1 - a1), sw * (x2 - a2)};
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc) {
-    if (d.prev) o[cc] += d.beta * d.prev[3 * t + cc];
+    if (d.prev) o[cc] += d.beta * pin[cc];
     out[3 * t + cc] = o[cc];
     val[cc] = o[cc];
     if (d.xacc) {
-      const double xa = d.xset ? o[cc] : d.xacc[3 * t + cc] + o[cc];
+      const double xa = d.xset ? o[cc] : ain[cc] + o[cc];
       d.xacc[3 * t + cc] = xa;
       if (d.prep_x) val[cc] = xa;
     }
@@ -1089,6 +1091,15 @@ __global__ __launch_bounds__(kTriThreads) void k_proj_small(const ProjData d, co
   ProjVert pv;
   pv.row[0] = pv.row[1] = -1;
   if (vert) pv = d.pvert[t];
+  // the last step's inputs that do not depend on x, loaded ahead of the barriers
+  double pin[3] = {0.0, 0.0, 0.0}, ain[3] = {0.0, 0.0, 0.0};
+  if (vert) {
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      if (d.prev) pin[cc] = d.prev[3 * t + cc];
+      if (d.xacc && !d.xset) ain[cc] = d.xacc[3 * t + cc];
+    }
+  }
   double acc[kProjSlots];
 #pragma unroll
   for (int q = 0; q < kProjSlots; ++q) acc[q] = 0.0;
@@ -1145,7 +1156,7 @@ __global__ __launch_bounds__(kTriThreads) void k_proj_small(const ProjData d, co
   }
   __syncthreads();
   double val[3] = {0.0, 0.0, 0.0};
-  if (vert) proj_small_vertex(d, t, out, pv, w_t, x0, x1, x2, yps, ybs, val);
+  if (vert) proj_small_vertex(d, t, out, pv, w_t, x0, x1, x2, yps, ybs, pin, ain, val);
   if (d.pp) proj_prep_operand<kTriThreads>(d, t, vert, val);
 }
 

@@ -489,11 +489,11 @@ __device__ __forceinline__ void sob_tile(const V4<R>* __restrict__ GA, const V4<
             const int2 ej = sE[u];
             const bool skip = (ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y);
             w = skip ? R(0) : w;
-            sob_edge_pair<R, EC, true>(a.x, a.y, a.z, b.x, b.y, b.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z, qb.x,
-                                       qb.y, qb.z, qt.x, qt.y, qt.z, skip ? R(1) : R(0), half_expo, rho, rho0);
+            sob_edge_pair<R, EC, true>(a.x, a.y, a.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z, qt.x, qt.y, qt.z, qa.w,
+                                       skip ? R(1) : R(0), half_expo, rho, rho0);
           } else {
-            sob_edge_pair<R, EC, false>(a.x, a.y, a.z, b.x, b.y, b.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z, qb.x,
-                                        qb.y, qb.z, qt.x, qt.y, qt.z, R(0), half_expo, rho, rho0);
+            sob_edge_pair<R, EC, false>(a.x, a.y, a.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z, qt.x, qt.y, qt.z, qa.w,
+                                        R(0), half_expo, rho, rho0);
           }
           const V4<R> sj = sS[u], uj = sU[u];
           const R wr = w * rho, w0 = w * rho0;

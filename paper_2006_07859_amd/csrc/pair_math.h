@@ -323,13 +323,44 @@ __device__ __forceinline__ void sob_edge_pair_d(R d11x, R d11y, R d11z, R d12x, 
   rho0 = fma(cJ2, q21 + q22, z);
 }
 
-// The same from the endpoints: target a, b (tangent T, length l_I), source c, e (tangent U).
+// The same from one endpoint of each edge: target a (tangent T, length l_I),
+// source c (tangent U, length l_J); the cross products and the tangential
+// component at the other endpoints are shifts by multiples of T x U and T.U
+// as in tpe_edge_pair.
 template <typename R, int EC, bool SKIP>
-__device__ __forceinline__ void sob_edge_pair(R ax, R ay, R az, R bx, R by, R bz, R Tx, R Ty, R Tz, R lI,
-                                              R cx, R cy, R cz, R ex, R ey, R ez, R Ux, R Uy, R Uz,
-                                              R skipv, R half_expo, R& rho, R& rho0) {
-  sob_edge_pair_d<R, EC, SKIP>(ax - cx, ay - cy, az - cz, ax - ex, ay - ey, az - ez, bx - cx, by - cy, bz - cz, Tx,
-                               Ty, Tz, lI, Ux, Uy, Uz, skipv, half_expo, rho, rho0);
+__device__ __forceinline__ void sob_edge_pair(R ax, R ay, R az, R Tx, R Ty, R Tz, R lI, R cx, R cy, R cz, R Ux,
+                                              R Uy, R Uz, R lJ, R skipv, R half_expo, R& rho, R& rho0) {
+  const R dx = ax - cx, dy = ay - cy, dz = az - cz;  // d(a, c)
+  const R wx = Ty * Uz - Tz * Uy, wy = Tz * Ux - Tx * Uz, wz = Tx * Uy - Ty * Ux;  // T x U
+  const R tu = Tx * Ux + Ty * Uy + Tz * Uz;
+  const R xIx = Ty * dz - Tz * dy, xIy = Tz * dx - Tx * dz, xIz = Tx * dy - Ty * dx;  // T x d(a, c)
+  const R yIx = xIx - lJ * wx, yIy = xIy - lJ * wy, yIz = xIz - lJ * wz;                // T x d(a, e)
+  const R xJx = Uy * dz - Uz * dy, xJy = Uz * dx - Ux * dz, xJz = Ux * dy - Uy * dx;  // U x d(a, c)
+  const R yJx = xJx - lI * wx, yJy = xJy - lI * wy, yJz = xJz - lI * wz;                // U x d(b, c)
+  R cI1 = xIx * xIx + xIy * xIy + xIz * xIz;
+  R cI2 = yIx * yIx + yIy * yIy + yIz * yIz;
+  if constexpr (SKIP) {
+    cI1 += skipv;
+    cI2 += skipv;
+  }
+  const R cJ1 = xJx * xJx + xJy * xJy + xJz * xJz;
+  const R cJ2 = yJx * yJx + yJy * yJy + yJz * yJz;
+  const R t11 = Tx * dx + Ty * dy + Tz * dz;
+  const R t12 = t11 - lJ * tu;
+  const R t21 = t11 + lI, t22 = t12 + lI;
+  const R r11 = t11 * t11 + cI1, r12 = t12 * t12 + cI2;
+  const R r21 = t21 * t21 + cI1, r22 = t22 * t22 + cI2;
+  R ri11, ri12, ri21, ri22, p11, p12, p21, p22;
+  sob_powers<EC, R>(r11, half_expo, ri11, p11);
+  sob_powers<EC, R>(r12, half_expo, ri12, p12);
+  sob_powers<EC, R>(r21, half_expo, ri21, p21);
+  sob_powers<EC, R>(r22, half_expo, ri22, p22);
+  rho = (p11 + p12) + (p21 + p22);
+  const R q11 = p11 * ri11 * ri11, q12 = p12 * ri12 * ri12, q21 = p21 * ri21 * ri21, q22 = p22 * ri22 * ri22;
+  R z = cI1 * (q11 + q21);
+  z = fma(cI2, q12 + q22, z);
+  z = fma(cJ1, q11 + q12, z);
+  rho0 = fma(cJ2, q21 + q22, z);
 }
 
 // ---------------------------------------------------------------------------
