@@ -185,6 +185,9 @@ __global__ __launch_bounds__(256) void k_assemble_lowp(
 // edges' geometry and the vertices' data are staged in LDS.  The pair terms
 // are evaluated with the smaller edge first and an entry sums its terms with
 // the smaller vertex's edges outermost, so that S^ is exactly symmetric.
+// Column tiles per workgroup of the edge-pair assembly (the row side is set up once for them).
+constexpr int kEpTiles = 8;
+
 struct EpEdge {
   double a[3], b[3];  // end points
   float t[3], l;      // unit tangent, length
@@ -262,8 +265,8 @@ __global__ __launch_bounds__(256) void k_assemble_lowp_ep(
   side_setup(0, rb * 16, 16);
   const int nr = nlist[0];
   double rs = 0.0, rs32 = 0.0;
-  for (int q = 0; q < 4; ++q) {
-    const int kt = blockIdx.y * 4 + q;
+  for (int q = 0; q < kEpTiles; ++q) {
+    const int kt = blockIdx.y * kEpTiles + q;
     if (kt >= nkt) break;  // uniform
     side_setup(1, kt * 32, 32);
     const int nc = nlist[1];
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(256) void k_assemble_lowp_ep(
       E[vl][wl] = sf;
     }
     __syncthreads();
-    if (wave == q) {  // the owning wave stores its lane vectors
+    if (wave == q % 4) {  // the owning wave stores its lane vectors
       typename Vec8<T>::type vec;
       float f[8];
       const int vl = l % 16, c0 = 8 * (l / 16);
@@ -807,12 +810,14 @@ template <typename T, int EC>
 static void assemble_t(const Curve& c, LowpOp& op, float half_expo, hipStream_t s) {
   typedef typename Vec8<T>::type V;
   dim3 grid(op.nrb, op.ngroups);
+  const dim3 grid_ep(op.nrb, cdiv(op.nkt, kEpTiles));
+  op.ngroups_used = c.max_degree <= 2 ? (int)grid_ep.y : op.ngroups;
   if (c.max_degree <= 2 && op.with32)
-    hipLaunchKernelGGL((k_assemble_lowp_ep<T, EC, true>), grid, dim3(256), 0, s, c.gd.a, c.gd.b, c.gd.t, c.edges,
+    hipLaunchKernelGGL((k_assemble_lowp_ep<T, EC, true>), grid_ep, dim3(256), 0, s, c.gd.a, c.gd.b, c.gd.t, c.edges,
                        c.inc_off, c.inc, c.edge_out, op.sqd, op.vinfo, op.band, op.n, op.nkt, half_expo,
                        (V*)op.tiles, (float4*)op.tiles32, op.rowpart, op.rowpart32);
   else if (c.max_degree <= 2)
-    hipLaunchKernelGGL((k_assemble_lowp_ep<T, EC, false>), grid, dim3(256), 0, s, c.gd.a, c.gd.b, c.gd.t, c.edges,
+    hipLaunchKernelGGL((k_assemble_lowp_ep<T, EC, false>), grid_ep, dim3(256), 0, s, c.gd.a, c.gd.b, c.gd.t, c.edges,
                        c.inc_off, c.inc, c.edge_out, op.sqd, op.vinfo, op.band, op.n, op.nkt, half_expo,
                        (V*)op.tiles, (float4*)nullptr, op.rowpart, (double*)nullptr);
   else if (op.with32)
@@ -850,10 +855,10 @@ rc_status launch_assemble_lowp(const Curve& c, LowpOp& op, int fmt, int band, bo
   if (fmt == 1) assemble_fmt<__bf16>(c, op, alpha, beta, s);
   else assemble_fmt<_Float16>(c, op, alpha, beta, s);
   const double* bp = op.band > 0 ? op.bandpart : nullptr;
-  hipLaunchKernelGGL(k_lowp_sigma, dim3(cdiv(op.n, 256)), dim3(256), 0, s, op.rowpart, op.ngroups, bp, op.sqd,
+  hipLaunchKernelGGL(k_lowp_sigma, dim3(cdiv(op.n, 256)), dim3(256), 0, s, op.rowpart, op.ngroups_used, bp, op.sqd,
                      op.n, op.sigma, diag_out);
   if (with32)
-    hipLaunchKernelGGL(k_lowp_sigma, dim3(cdiv(op.n, 256)), dim3(256), 0, s, op.rowpart32, op.ngroups, bp, op.sqd,
+    hipLaunchKernelGGL(k_lowp_sigma, dim3(cdiv(op.n, 256)), dim3(256), 0, s, op.rowpart32, op.ngroups_used, bp, op.sqd,
                        op.n, op.sigma32, (double*)nullptr);
   hipLaunchKernelGGL(k_lowp_prep_static, dim3(cdiv(op.nkt * 96, 256)), dim3(256), 0, s, op.sqd, op.n, op.nkt, op.pbuf,
                      op.sqdf);

@@ -213,6 +213,7 @@ struct LowpOp {
   int n = 0, fmt = 0, band = 0;
   bool with32 = false;
   int nrb = 0, nkt = 0, ngroups = 0, nsplit = 1, per = 0;  // column-tile splits of the 16-bit product
+  int ngroups_used = 0;  // column-tile groups of the last assembly (rows of rowpart it wrote)
   int nsplit32 = 1, per32 = 0;                               // and of the FP32 product
   void* tiles = nullptr;        // [nrb][nkt][64 lanes] 16-byte vectors of 8 16-bit values
   void* tiles32 = nullptr;      // [nrb][nkt][64 lanes] 8 floats
