@@ -375,22 +375,27 @@ __global__ void k_lowp_band(const V4<double>* __restrict__ GA, const V4<double>*
                             const double* __restrict__ edge_out, const double* __restrict__ sqd,
                             const int* __restrict__ band_idx, int band, int n, double half_expo,
                             float* __restrict__ band_val, double* __restrict__ bandpart) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
+  // 32 lanes per vertex: lane q computes slots q, q + 32, ..., and the row sum
+  // is reduced over the lanes in a fixed order
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = g / 32, q = g % 32;
   const int nb = 2 * band;
   double rs = 0.0;
-  for (int q = 0; q < nb; ++q) {
-    const int w = band_idx[(size_t)v * nb + q];
-    float val = 0.f;
-    if (w >= 0) {
-      const double a =
-          sobolev_entry<double, EC>(min(v, w), max(v, w), GA, GB, GT, edges, inc_off, inc, edge_out, half_expo);
-      val = (float)(a / (sqd[v] * sqd[w]));
-      rs += (double)val * sqd[w];
+  if (v < n)
+    for (int qq = q; qq < nb; qq += 32) {
+      const int w = band_idx[(size_t)v * nb + qq];
+      float val = 0.f;
+      if (w >= 0) {
+        const double a =
+            sobolev_entry<double, EC>(min(v, w), max(v, w), GA, GB, GT, edges, inc_off, inc, edge_out, half_expo);
+        val = (float)(a / (sqd[v] * sqd[w]));
+        rs += (double)val * sqd[w];
+      }
+      band_val[(size_t)v * nb + qq] = val;
     }
-    band_val[(size_t)v * nb + q] = val;
-  }
-  bandpart[v] = rs;
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) rs += __shfl_xor(rs, off, 32);
+  if (v < n && q == 0) bandpart[v] = rs;
 }
 
 // sigma_off_v = -(sum of the tile row parts) / sqrt(d_v): the diagonal that
@@ -829,7 +834,7 @@ static void assemble_t(const Curve& c, LowpOp& op, float half_expo, hipStream_t 
                        c.inc_off, c.inc, c.edge_out, op.sqd, op.vinfo, op.band, op.n, op.nkt, half_expo,
                        (V*)op.tiles, (float4*)nullptr, op.rowpart, (double*)nullptr);
   if (op.band > 0)
-    hipLaunchKernelGGL((k_lowp_band<EC>), dim3(cdiv(op.n, 64)), dim3(64), 0, s, c.gd.a, c.gd.b, c.gd.t, c.edges,
+    hipLaunchKernelGGL((k_lowp_band<EC>), dim3(cdiv(op.n * 32, 256)), dim3(256), 0, s, c.gd.a, c.gd.b, c.gd.t, c.edges,
                        c.inc_off, c.inc, c.edge_out, op.sqd, op.band_idx, op.band, op.n, (double)half_expo,
                        op.band_val, op.bandpart);
 }

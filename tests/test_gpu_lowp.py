@@ -61,7 +61,7 @@ def ctx_for(g, e, a, b):
 
 
 @pytest.mark.parametrize("fmt", [1, 2])
-@pytest.mark.parametrize("band", [0, 16])
+@pytest.mark.parametrize("band", [0, 16, 40])
 @pytest.mark.parametrize("alpha,beta", [(2.0, 4.5), (3.0, 6.0)])
 def test_single_product_bound(lib, fmt, band, alpha, beta):
     n = 1000  # 63 row blocks, 32 column tiles: ragged in both directions
