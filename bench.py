@@ -147,7 +147,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not supported "
-                                   "(the sharding design is described in DESIGN.md)", "n_gpus": args.gpus}))
+                                   "(the path is built and measured on one GPU's share)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     if args.workload == "bh":
