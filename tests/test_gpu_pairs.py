@@ -83,6 +83,32 @@ def test_small_and_multi_component(lib):
         assert relnorm(host(dE), G_ref) < 10 * tol
 
 
+def test_f32_band_tiles_of_several_chains(lib):
+    """FP32 energy + differential with the chain band on a network of two loops and an open path,
+    each several 256-edge tiles long, in chain order and then shuffled: the tiles hold one chain
+    (near and far along it, also across a loop's wrap), two chains, or chains whose ranges are
+    disjoint, so every branch of the per-tile band classification runs against the oracle."""
+    from paper_2006_07859_amd import RC_F32
+
+    banner("energy+dE f32 two loops + open path, several tiles per chain")
+    g1, e1, _ = gen.fourier_knot(700, seed=5)
+    g2, e2, _ = gen.fourier_knot(600, seed=6)
+    g2 = g2 + [4.0, 0.0, 0.0]
+    t = np.linspace(0.0, 1.0, 401)
+    g3 = np.stack([0.4 * np.cos(6 * t), 3.0 + 0.4 * np.sin(6 * t), 2.0 * t], 1)
+    e3 = np.stack([np.arange(400), np.arange(1, 401)], 1)
+    g = gen.round_to_f32(np.concatenate([g1, g2, g3]))
+    e_ordered = np.concatenate([e1, e2 + 700, e3 + 1300]).astype(np.int32)
+    e_shuffled = e_ordered[np.random.default_rng(1).permutation(len(e_ordered))]
+    for e in (e_ordered, e_shuffled):
+        E_ref, G_ref = tpe.differential(g, e, 2.0, 4.5)
+        ctx = ctx_for(lib, g, e, 2.0, 4.5, RC_F32)
+        E, dE = zeros(1), zeros(len(g), 3)
+        ctx.rc_differential(dev(g), E, dE)
+        assert host(E)[0] == pytest.approx(E_ref, rel=1e-5)
+        assert relnorm(host(dE), G_ref) < 1e-4
+
+
 def test_triangle_has_zero_energy(lib):
     from paper_2006_07859_amd import RC_F64
 
