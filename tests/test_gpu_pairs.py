@@ -187,6 +187,35 @@ def test_operator_apply_and_diag(lib, alpha, beta):
     assert np.abs(host(Y)).max() < 1e-9 * np.abs(A).max()
 
 
+def test_operator_tiles_of_several_chains(lib):
+    """The operator A = B + B0 applied matrix-free (FP64 and FP32) on two loops and an open path,
+    each several 256-edge tiles long, in chain order and shuffled: tiles whose vertex ranges are
+    disjoint skip the per-pair shared-vertex test, the others keep it."""
+    from paper_2006_07859_amd import RC_F32, RC_F64
+
+    banner("operator apply f64/f32 two loops + open path, several tiles per chain")
+    g1, e1, _ = gen.fourier_knot(700, seed=5)
+    g2, e2, _ = gen.fourier_knot(600, seed=6)
+    g2 = g2 + [4.0, 0.0, 0.0]
+    t = np.linspace(0.0, 1.0, 401)
+    g3 = np.stack([0.4 * np.cos(6 * t), 3.0 + 0.4 * np.sin(6 * t), 2.0 * t], 1)
+    e3 = np.stack([np.arange(400), np.arange(1, 401)], 1)
+    g = gen.round_to_f32(np.concatenate([g1, g2, g3]))
+    n = len(g)
+    e_ordered = np.concatenate([e1, e2 + 700, e3 + 1300]).astype(np.int32)
+    e_shuffled = e_ordered[np.random.default_rng(2).permutation(len(e_ordered))]
+    X = np.random.default_rng(3).normal(size=(n, 3))
+    B, B0 = sobolev.assemble(g, e_ordered, 2.0, 4.5)
+    ref = (B + B0) @ X
+    for e in (e_ordered, e_shuffled):
+        ctx = ctx_for(lib, g, e, 2.0, 4.5, RC_F64)
+        Y = zeros(n, 3)
+        ctx.rc_sobolev_apply(dev(g), dev(X), Y, prec=RC_F64)
+        assert relnorm(host(Y), ref) < 1e-10
+        ctx.rc_sobolev_apply(dev(g), dev(X), Y, prec=RC_F32)
+        assert relnorm(host(Y), ref) < 1e-5
+
+
 @pytest.mark.parametrize("alpha,beta", [(2.0, 4.0), (2.0, 4.5), (3.0, 6.0)])
 def test_dense_assembly(lib, alpha, beta):
     from paper_2006_07859_amd import RC_F64
