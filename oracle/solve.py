@@ -92,7 +92,8 @@ def projection_increment_transform(A, C, phi):
 
 
 def _phi_tolerance(gamma, edges, mask):
-    """Per-row projection tolerance: 1e-10 l_mean (lengths), 1e-10 L l_mean (barycenter)."""
+    """Per-row projection tolerance: 1e-10 l_mean (edge lengths), 1e-10 L l_mean
+    (barycenter), 1e-10 L (total length) and 1e-10 L_q (length of loop q)."""
     ell, _, _ = tpe.edge_geometry(gamma, edges)
     lbar, L = ell.mean(), ell.sum()
     tol = []
@@ -102,16 +103,22 @@ def _phi_tolerance(gamma, edges, mask):
         tol += [1e-10 * L]
     if mask & cons.EDGE_LENGTH:
         tol += [1e-10 * lbar] * len(edges)
+    if mask & cons.LOOP_LENGTH:
+        tol += list(1e-10 * cons.loop_lengths(gamma, edges))
     return np.array(tol)
 
 
 def project(gamma_t, edges, A, C, mask, refs, max_iter=10, tol=None):
-    """Iterate the projection increment from gamma_t; returns (gamma, iters, ok)."""
-    x0, L0, l0 = refs
+    """Iterate the projection increment from gamma_t; returns (gamma, iters, ok).
+
+    ``refs`` is ``(x0, L0, l0)`` or ``(x0, L0, l0, Lq)`` with the loop-length
+    targets ``Lq`` (needed when ``mask`` has LOOP_LENGTH)."""
+    x0, L0, l0 = refs[:3]
+    Lq = refs[3] if len(refs) > 3 else None
     g = np.array(gamma_t, dtype=np.float64)
     tol = _phi_tolerance(g, edges, mask) if tol is None else tol
     for it in range(max_iter + 1):
-        phi, _ = cons.evaluate(g, edges, mask, x0, L0, l0, jacobian=False)
+        phi, _ = cons.evaluate(g, edges, mask, x0, L0, l0, jacobian=False, Lq=Lq)
         if np.all(np.abs(phi) <= tol):
             return g, it, True
         if it == max_iter:
@@ -142,8 +149,8 @@ def step(gamma, edges, alpha, beta, mask, refs):
     E0, dE = tpe.differential(gamma, edges, alpha, beta)
     B, B0 = sobolev.assemble(gamma, edges, alpha, beta)
     A = B + B0
-    x0, L0, l0 = refs
-    _, C = cons.evaluate(gamma, edges, mask, x0, L0, l0)
+    x0, L0, l0 = refs[:3]
+    _, C = cons.evaluate(gamma, edges, mask, x0, L0, l0, Lq=refs[3] if len(refs) > 3 else None)
     g, _ = projected_gradient(A, C, dE)
     new, tau, E1, info = line_search(gamma, edges, alpha, beta, E0, dE, g, A, C, mask, refs)
     info.update(E0=E0, E1=E1, tau=tau, g=g, dE=dE)

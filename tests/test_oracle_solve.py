@@ -150,3 +150,16 @@ def test_loop_length_saddle_kkt():
     assert np.abs(C @ gt.ravel()).max() < 1e-10 * np.abs(gt).max()
     kkt = np.kron(A, np.eye(3)) @ gt.ravel() + C.T @ lam - dE.ravel()
     assert np.abs(kkt).max() < 1e-9 * np.abs(dE).max()
+
+
+def test_loop_length_step_restores_every_loop():
+    # the projection's tolerance has one row per loop (1e-10 times its length)
+    g, e = two_loops()
+    refs = cons.reference_values(g, e) + (cons.loop_lengths(g, e),)
+    mask = cons.BARYCENTER | cons.LOOP_LENGTH
+    new, info = solve.step(g, e, 3.0, 6.0, mask, refs)
+    assert info["ok"] and info["E1"] < info["E0"]
+    phi, _ = cons.evaluate(new, e, mask, refs[0], Lq=refs[3], jacobian=False)
+    assert np.abs(phi[3:]).max() <= 1e-10 * refs[3].max()
+    assert np.abs(phi[:3]).max() <= 1e-10 * refs[1] * refs[2].mean()
+    assert np.allclose(cons.loop_lengths(new, e), refs[3], rtol=1e-10)
