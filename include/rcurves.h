@@ -23,7 +23,13 @@
  * - Errors: argument and parameter errors are returned synchronously and
  *   leave outputs untouched.  Every call returns RC_OK on success.
  *   rc_last_error() gives a human-readable message for the last failure on
- *   the calling thread.
+ *   the calling thread.  Conditions found on the device (non-finite input,
+ *   a zero-length edge, coincident vertices of disjoint edges, a non-finite
+ *   energy or differential) do not stop the stream: the kernel that finds
+ *   one latches an RC_FLAG_* bit into the context's device status word, and
+ *   the solver's own failures (no convergence, singular factorisation,
+ *   projection, line search) latch theirs too; rc_sync_status() reads and
+ *   clears them.
  * - One context per stream; contexts are independent and not thread-safe.
  */
 #ifndef RCURVES_H
@@ -55,6 +61,23 @@ typedef enum {
 } rc_status;
 
 typedef enum { RC_F64 = 0, RC_F32 = 1 } rc_dtype;
+
+/* Bits of the status word (rc_stats.flags after rc_sync_status).  The first
+ * four are set on the device by the kernel that meets the condition; the
+ * others by the calls that return the matching rc_status. */
+enum {
+  RC_FLAG_INPUT_NONFINITE = 1u << 0,  /* a vertex coordinate is Inf or NaN (RC_ERR_NONFINITE) */
+  RC_FLAG_ZERO_EDGE = 1u << 1,        /* an edge of length 0: T_I undefined (RC_ERR_DEGENERATE) */
+  RC_FLAG_PAIR_OVERFLOW = 1u << 2,    /* a pair sum of a finite, non-degenerate edge is not finite:
+                                         coincident (or nearly coincident) vertices of disjoint edges,
+                                         where the energy of Sec. 4.1 is infinite (RC_ERR_DEGENERATE) */
+  RC_FLAG_RESULT_NONFINITE = 1u << 3, /* an energy or differential entry is Inf or NaN (RC_ERR_NONFINITE);
+                                         also set by an obstacle penalty that a midpoint reaches */
+  RC_FLAG_NOT_CONVERGED = 1u << 4,    /* RC_ERR_NOT_CONVERGED was returned */
+  RC_FLAG_SINGULAR = 1u << 5,         /* RC_ERR_SINGULAR was returned */
+  RC_FLAG_PROJECTION = 1u << 6,       /* RC_ERR_PROJECTION was returned */
+  RC_FLAG_LINESEARCH = 1u << 7        /* RC_ERR_LINESEARCH was returned */
+};
 
 /* Constraint flags (paper Sec. 7.1). */
 enum {
@@ -147,7 +170,19 @@ typedef struct {
   double t_solve_ms;     /* rc_step: constraint/multigrid setup + gradient solve */
   double t_search_ms;    /* rc_step: line search with projection */
   int32_t fallback;      /* 1 when the gradient solve fell back to the multigrid preconditioner */
+  uint32_t flags;        /* rc_sync_status: the RC_FLAG_* bits latched since the last read */
 } rc_stats;
+
+/* Waits for the context's stream, reads the RC_FLAG_* bits latched since the
+ * last call (device word and solver word), clears them, and returns the status
+ * they mean, in the order input non-finite (RC_ERR_NONFINITE), zero-length
+ * edge or pair overflow (RC_ERR_DEGENERATE, Lemma FiniteTangentPointEnergy and
+ * Sec. 4.1: the energy of coincident points of disjoint edges is infinite),
+ * non-finite result (RC_ERR_NONFINITE), RC_ERR_SINGULAR, RC_ERR_NOT_CONVERGED,
+ * RC_ERR_PROJECTION, RC_ERR_LINESEARCH; RC_OK when none is set.
+ * out_h (host, may be NULL): status and flags are written, other fields are
+ * left as they are. */
+rc_status rc_sync_status(rc_ctx* ctx, rc_stats* out_h);
 
 /* Default option values. */
 void rc_default_solve_opts(rc_solve_opts* o);
@@ -443,7 +478,8 @@ rc_status rc_learned_train_step(rc_ctx* ctx, const double* gamma, const double* 
  * kernel on the finest level (coarse multigrid levels are not timed), 2: the
  * 16-bit assembled product kernel on the finest level, 3: the FP32 assembled
  * product kernel, 4: the FP64 operator pair kernel on the finest level, 5: the
- * batch's assembled per-instance product (not recorded inside a captured step). */
+ * batch's assembled per-instance product (not recorded inside a captured step),
+ * 6: the Barnes-Hut traversal kernel. */
 rc_status rc_profile_enable(rc_ctx* ctx, int32_t enable);
 rc_status rc_profile_read(rc_ctx* ctx, int32_t which, double* total_ms, int32_t* launches);
 

@@ -36,8 +36,11 @@ EXPORTED = [
     "rc_batch_set_constraints", "rc_batch_gradient", "rc_batch_step", "rc_batch_pcg_state", "rc_batch_autotune",
     "rc_batch_sobolev_apply", "rc_mlp_n_params", "rc_mlp_create", "rc_mlp_destroy", "rc_mlp_get", "rc_mlp_set", "rc_mlp_forward",
     "rc_mlp_backward", "rc_mlp_adam", "rc_learned_attach", "rc_learned_levels", "rc_learned_features",
-    "rc_learned_scalings", "rc_learned_apply", "rc_learned_train_step",
+    "rc_learned_scalings", "rc_learned_apply", "rc_learned_train_step", "rc_sync_status",
 ]
+
+RC_FLAG_INPUT_NONFINITE, RC_FLAG_ZERO_EDGE, RC_FLAG_PAIR_OVERFLOW, RC_FLAG_RESULT_NONFINITE = 1, 2, 4, 8
+RC_FLAG_NOT_CONVERGED, RC_FLAG_SINGULAR, RC_FLAG_PROJECTION, RC_FLAG_LINESEARCH = 16, 32, 64, 128
 
 
 class RcError(RuntimeError):
@@ -72,7 +75,7 @@ class Stats(C.Structure):
                 ("residual", C.c_double), ("tau", C.c_double), ("iterations", C.c_int32),
                 ("proj_solve_iterations", C.c_int32), ("backtracks", C.c_int32), ("proj_iters", C.c_int32),
                 ("status", C.c_int32), ("sweeps", C.c_int32), ("t_eval_ms", C.c_double), ("t_solve_ms", C.c_double),
-                ("t_search_ms", C.c_double), ("fallback", C.c_int32)]
+                ("t_search_ms", C.c_double), ("fallback", C.c_int32), ("flags", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -138,6 +141,7 @@ def load():
         "rc_mlp_backward": (I32, [P, P, I32, P, P]),
         "rc_mlp_adam": (I32, [P, P, C.c_float]),
         "rc_learned_attach": (I32, [P, P]),
+        "rc_sync_status": (I32, [P, C.POINTER(Stats)]),
         "rc_learned_levels": (I32, [P, I32, P, I32, C.POINTER(I32)]),
         "rc_learned_features": (I32, [P, P, I32, P, P]),
         "rc_learned_scalings": (I32, [P, P, I32, P]),
@@ -302,6 +306,12 @@ class Context:
         l = ls if ls is not None else default_ls_opts()
         _check(load().rc_step(self.h, self._v(gamma, "gamma"), C.byref(o), C.byref(l), C.byref(st)))
         return st.as_dict()
+
+    def rc_sync_status(self):
+        """(status, flags): the rc_status the latched RC_FLAG_* bits mean, and the bits (then cleared)."""
+        st = Stats()
+        status = load().rc_sync_status(self.h, C.byref(st))
+        return int(status), int(st.flags)
 
     def rc_bh_differential(self, gamma, theta, leaf_size, energy, dE):
         _check(load().rc_bh_differential(self.h, self._v(gamma, "gamma"), float(theta), int(leaf_size),

@@ -165,6 +165,9 @@ static rc_status create_ctx(int32_t nV, int32_t nE, const int32_t* edges_h, doub
   RC_TRY(dalloc(&c->scal, 64));
   RC_TRY(dalloc(&c->red, (size_t)dot_scratch_size(128)));
   RC_TRY(dalloc(&c->phi, 2 * ((size_t)nE + 4)));
+  RC_TRY(dalloc(&c->status_dev, 1));
+  RC_HIP(hipMemsetAsync(c->status_dev, 0, sizeof(unsigned), c->stream));
+  c->curve.status = c->status_dev;
   RC_HIP(hipMemsetAsync(c->x, 0, sizeof(double) * n3, c->stream));
   RC_TRY(sync(c.get()));
   *out = c.release();
@@ -203,8 +206,51 @@ rc_status rc_destroy(rc_ctx* c) {
                   c->red,  c->trial, c->zmin, c->inc, c->phi, c->dx, c->dEs,  c->gs};
   for (double* p : ps)
     if (p) hipFree(p);
+  if (c->status_dev) hipFree(c->status_dev);
   delete c;
   return RC_OK;
+}
+
+// The RC_FLAG_* bit of a status returned by a solver call (0 for the others).
+static unsigned flag_of(rc_status st) {
+  switch (st) {
+    case RC_ERR_NOT_CONVERGED: return RC_FLAG_NOT_CONVERGED;
+    case RC_ERR_SINGULAR: return RC_FLAG_SINGULAR;
+    case RC_ERR_PROJECTION: return RC_FLAG_PROJECTION;
+    case RC_ERR_LINESEARCH: return RC_FLAG_LINESEARCH;
+    default: return 0u;
+  }
+}
+
+static rc_status latch_host(rc_ctx* c, rc_status st) {
+  c->status_host |= flag_of(st);
+  return st;
+}
+
+rc_status rc_sync_status(rc_ctx* c, rc_stats* out) {
+  RC_TRY(check_ctx(c));
+  unsigned dev = 0;
+  RC_HIP(hipMemcpyAsync(&dev, c->status_dev, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+  RC_HIP(hipMemsetAsync(c->status_dev, 0, sizeof(unsigned), c->stream));
+  RC_HIP(hipStreamSynchronize(c->stream));
+  const unsigned f = dev | c->status_host;
+  c->status_host = 0;
+  static const struct { unsigned bit; rc_status st; } order[] = {
+      {RC_FLAG_INPUT_NONFINITE, RC_ERR_NONFINITE}, {RC_FLAG_ZERO_EDGE, RC_ERR_DEGENERATE},
+      {RC_FLAG_PAIR_OVERFLOW, RC_ERR_DEGENERATE},  {RC_FLAG_RESULT_NONFINITE, RC_ERR_NONFINITE},
+      {RC_FLAG_SINGULAR, RC_ERR_SINGULAR},         {RC_FLAG_NOT_CONVERGED, RC_ERR_NOT_CONVERGED},
+      {RC_FLAG_PROJECTION, RC_ERR_PROJECTION},     {RC_FLAG_LINESEARCH, RC_ERR_LINESEARCH}};
+  rc_status st = RC_OK;
+  for (const auto& o : order)
+    if (f & o.bit) {
+      st = o.st;
+      break;
+    }
+  if (out) {
+    out->status = st;
+    out->flags = f;
+  }
+  return st;
 }
 
 rc_status rc_energy(rc_ctx* c, const double* gamma, double* energy) {
@@ -311,7 +357,7 @@ rc_status rc_sobolev_gradient(rc_ctx* c, const double* gamma, const double* dE, 
   rc_solve_opts o = resolve(opts);
   int iters = 0, fell = 0;
   double res = 0.0;
-  rc_status st = solve_gradient(c, gamma, dE, g, o, &iters, &res, &fell);
+  rc_status st = latch_host(c, solve_gradient(c, gamma, dE, g, o, &iters, &res, &fell));
   if (stats) {
     stats->iterations = iters;
     stats->residual = res;
@@ -331,7 +377,7 @@ rc_status rc_line_search_step(rc_ctx* c, double* gamma, double energy0, const do
   rc_ls_opts l = resolve_ls(ls);
   RC_TRY(prepare_solver(c, gamma, o));
   LsResult r;
-  rc_status st = line_search(c, gamma, energy0, dE, g, l, o, &r);
+  rc_status st = latch_host(c, line_search(c, gamma, energy0, dE, g, l, o, &r));
   if (tau_h) *tau_h = r.tau;
   if (stats) {
     stats->tau = r.tau;
@@ -403,6 +449,7 @@ rc_status rc_step(rc_ctx* c, double* gamma, const rc_solve_opts* so, const rc_ls
   if (nev > 3 && hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) local.t_search_ms = ms;
   for (hipEvent_t e : ev) hipEventDestroy(e);
   local.status = st;
+  latch_host(c, st);
   if (stats) *stats = local;
   return st;
 }
@@ -429,16 +476,17 @@ extern "C" rc_status rc_profile_enable(rc_ctx* c, int32_t enable) {
 extern "C" rc_status rc_profile_read(rc_ctx* c, int32_t which, double* total_ms, int32_t* launches) {
   RC_TRY(check_ctx(c));
   RC_TRY(check_ptrs({total_ms, launches}));
-  if (which < 0 || which > 5) {
+  if (which < 0 || which > 6) {
     set_error("rc_profile_read: which must be 0 (energy+differential pairs), 1 (FP32 operator pairs), 2 "
-              "(assembled 16-bit product), 3 (assembled FP32 product), 4 (FP64 operator pairs) or 5 (batch "
-              "assembled product)");
+              "(assembled 16-bit product), 3 (assembled FP32 product), 4 (FP64 operator pairs), 5 (batch "
+              "assembled product) or 6 (Barnes-Hut traversal)");
     return RC_ERR_ARG;
   }
   RC_HIP(hipStreamSynchronize(c->stream));
   const std::vector<hipEvent_t>& v =
       which == 0 ? c->timer.tpe : which == 1 ? c->timer.sob : which == 2 ? c->timer.lowp
-                                : which == 3 ? c->timer.asm32 : which == 4 ? c->timer.sob64 : c->timer.basm;
+                                : which == 3 ? c->timer.asm32 : which == 4 ? c->timer.sob64
+                                : which == 5 ? c->timer.basm : c->timer.bh;
   double tot = 0.0;
   for (size_t i = 0; i + 1 < v.size(); i += 2) {
     float ms = 0.f;

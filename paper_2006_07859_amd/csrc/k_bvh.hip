@@ -543,6 +543,8 @@ rc_status launch_bh(const Curve& c, Bvh& bvh, double alpha, double beta, double 
   hipLaunchKernelGGL(k_invperm, dim3(cdiv(nE, 256)), dim3(256), 0, s, bvh.perm, nE, bvh.scratch);
   const float ha = (float)(0.5 * alpha), hb = (float)(0.5 * beta), bb = (float)beta, th = (float)theta;
   dim3 g(cdiv(nE, 256)), b(256);
+  const bool timed = c.timer && c.timer->on;
+  if (timed) c.timer->mark(c.timer->bh, s);
 #define RC_BH(EC, BAND)                                                                                            \
   hipLaunchKernelGGL((k_bh_traverse<EC, BAND>), g, b, 0, s, c.gf.a, c.gf.b, c.gf.t, c.gd.a, c.gd.b, c.gd.t, c.edges, \
                      c.inc_off, c.inc, c.cinfo, nE, bvh.perm, bvh.scratch, bvh.node, bvh.na, bvh.nb, bvh.nr, th, ha, \
@@ -557,6 +559,7 @@ rc_status launch_bh(const Curve& c, Bvh& bvh, double alpha, double beta, double 
   }
 #undef RC_BH2
 #undef RC_BH
+  if (timed) c.timer->mark(c.timer->bh, s);
   RC_HIP(hipGetLastError());
   return finalize_midpoint(c, 1, energy, dE, s);
 }

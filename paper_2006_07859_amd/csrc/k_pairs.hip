@@ -34,9 +34,12 @@ ExpCase exp_case(double alpha, double beta) {
 // ---------------------------------------------------------------------------
 // edge geometry: FP64 state -> rounded SoA in the kernel precision
 // ---------------------------------------------------------------------------
+// The FP64 pass (status != null) latches a non-finite coordinate and a
+// zero-length edge (l_I = 0: T_I is undefined, Sec. 4 Notation).
 template <typename R>
 __global__ void k_geometry(const double* __restrict__ gamma, const int2* __restrict__ edges, int nE,
-                           V4<R>* __restrict__ A, V4<R>* __restrict__ B, V4<R>* __restrict__ T) {
+                           V4<R>* __restrict__ A, V4<R>* __restrict__ B, V4<R>* __restrict__ T,
+                           unsigned* __restrict__ status) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nE) return;
   int2 e = edges[I];
@@ -44,6 +47,11 @@ __global__ void k_geometry(const double* __restrict__ gamma, const int2* __restr
   double q0 = gamma[3 * e.y], q1 = gamma[3 * e.y + 1], q2 = gamma[3 * e.y + 2];
   double d0 = q0 - p0, d1 = q1 - p1, d2 = q2 - p2;
   double l = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  if (status) {
+    const bool fin = isfinite(p0) & isfinite(p1) & isfinite(p2) & isfinite(q0) & isfinite(q1) & isfinite(q2);
+    if (!fin) latch(status, kFlagInputNonfinite);
+    else if (!(l > 0.0)) latch(status, kFlagZeroEdge);
+  }
   double il = 1.0 / l;
   A[I] = V4<R>{R(p0), R(p1), R(p2), R(l)};
   B[I] = V4<R>{R(q0), R(q1), R(q2), R(0)};
@@ -335,10 +343,14 @@ __device__ __forceinline__ void sum_chunks4(const double* __restrict__ part, int
 // partials: edge_out[I] = (E_I, dE/dg_i1 (3), dE/dg_i2 (3), -).
 // Chunks 0 .. n - 1 with n = nch_e[I] (batch) or nchunk, then the near-band
 // chunk `band_chunk` when it is >= 0.  64 edges per workgroup of 256 threads.
+// A non-finite pair sum of an edge with a finite length means that a disjoint
+// pair's kernel overflowed: coincident (or nearly coincident) vertices of
+// disjoint edges, where the energy is infinite (Sec. 4.1); it is latched.
 __global__ __launch_bounds__(256) void k_tpe_finalize(const double* __restrict__ part, int nchunk,
                                                       const int* __restrict__ nch_e, int band_chunk, int nE, int grad,
                                                       const double* __restrict__ gd_a,
-                                                      const double* __restrict__ gd_t, double* __restrict__ edge_out) {
+                                                      const double* __restrict__ gd_t, double* __restrict__ edge_out,
+                                                      unsigned* __restrict__ status) {
   const int I = blockIdx.x * 64 + threadIdx.x % 64;
   const bool valid = I < nE;
   const int NS = grad ? kTpeSlots : 1;
@@ -349,6 +361,10 @@ __global__ __launch_bounds__(256) void k_tpe_finalize(const double* __restrict__
   const double l = gd_a[4 * I + 3];
   double* o = edge_out + 8 * (size_t)I;
   o[0] = l * s[0];
+  bool fin = isfinite(s[0]);
+  if (grad)
+    for (int k = 1; k < kTpeSlots; ++k) fin &= isfinite(s[k]);
+  if (!fin && isfinite(l) && l > 0.0) latch(status, kFlagPairOverflow);
   if (!grad) return;
   const double Tx = gd_t[4 * I], Ty = gd_t[4 * I + 1], Tz = gd_t[4 * I + 2];
   const double S = s[1];
@@ -363,7 +379,8 @@ __global__ __launch_bounds__(256) void k_tpe_finalize(const double* __restrict__
 
 // dE_v = sum over incident (edge, endpoint) of the edge's endpoint partial.
 __global__ void k_gather_vertex(const double* __restrict__ edge_out, const int* __restrict__ inc_off,
-                                const int* __restrict__ inc, int nV, double* __restrict__ dE) {
+                                const int* __restrict__ inc, int nV, double* __restrict__ dE,
+                                unsigned* __restrict__ status) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nV) return;
   double gx = 0, gy = 0, gz = 0;
@@ -377,6 +394,7 @@ __global__ void k_gather_vertex(const double* __restrict__ edge_out, const int* 
   dE[3 * v] = gx;
   dE[3 * v + 1] = gy;
   dE[3 * v + 2] = gz;
+  if (!(isfinite(gx) & isfinite(gy) & isfinite(gz))) latch(status, kFlagResultNonfinite);
 }
 
 // Deterministic sum of edge_out[8 I + slot] over I: per-block partials, then one block.
@@ -393,7 +411,8 @@ __global__ void k_sum_slot(const double* __restrict__ edge_out, int slot, int n,
   if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
 }
 
-__global__ void k_sum_partials(const double* __restrict__ partial, int n, double* __restrict__ out) {
+__global__ void k_sum_partials(const double* __restrict__ partial, int n, double* __restrict__ out,
+                               unsigned* __restrict__ status) {
   __shared__ double sm[256];
   double v = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) v += partial[i];
@@ -403,13 +422,16 @@ __global__ void k_sum_partials(const double* __restrict__ partial, int n, double
     if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = sm[0];
+  if (threadIdx.x == 0) {
+    out[0] = sm[0];
+    if (!isfinite(sm[0])) latch(status, kFlagResultNonfinite);
+  }
 }
 
 static void sum_edge_slot(const Curve& c, int slot, double* out, hipStream_t s) {
   int nb = c.red_blocks;
   hipLaunchKernelGGL(k_sum_slot, dim3(nb), dim3(256), 0, s, c.edge_out, slot, c.nE, c.red);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, c.red, nb, out);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, c.red, nb, out, c.status);
 }
 
 // ---------------------------------------------------------------------------
@@ -718,7 +740,7 @@ __global__ void k_mid_band(const V4<double>* __restrict__ GA, const V4<double>* 
 
 __global__ void k_mid_finalize(const double* __restrict__ part, int nchunk, int nE,
                                const double* __restrict__ gd_a, const double* __restrict__ gd_t,
-                               double* __restrict__ edge_out) {
+                               double* __restrict__ edge_out, unsigned* __restrict__ status) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nE) return;
   double s[kMidSlotsUsed];
@@ -728,6 +750,9 @@ __global__ void k_mid_finalize(const double* __restrict__ part, int nchunk, int 
     s[k] = v;
   }
   const double l = gd_a[4 * I + 3];
+  bool fin = true;
+  for (int k = 0; k < kMidSlotsUsed; ++k) fin &= isfinite(s[k]);
+  if (!fin && isfinite(l) && l > 0.0) latch(status, kFlagPairOverflow);
   const double Tx = gd_t[4 * I], Ty = gd_t[4 * I + 1], Tz = gd_t[4 * I + 2];
   const double S = s[1];
   const double Hx = s[6] - s[9] * Tx, Hy = s[7] - s[9] * Ty, Hz = s[8] - s[9] * Tz;
@@ -874,9 +899,10 @@ static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 rc_status launch_geometry(const Curve& c, const double* gamma, rc_dtype prec, hipStream_t s) {
   dim3 g(cdiv(c.nE, 256)), b(256);
   if (prec == RC_F32)
-    hipLaunchKernelGGL(k_geometry<float>, g, b, 0, s, gamma, c.edges, c.nE, c.gf.a, c.gf.b, c.gf.t);
+    hipLaunchKernelGGL(k_geometry<float>, g, b, 0, s, gamma, c.edges, c.nE, c.gf.a, c.gf.b, c.gf.t,
+                       (unsigned*)nullptr);
   // the FP64 copy is always kept: the finalize kernels read l_I and T_I from it
-  hipLaunchKernelGGL(k_geometry<double>, g, b, 0, s, gamma, c.edges, c.nE, c.gd.a, c.gd.b, c.gd.t);
+  hipLaunchKernelGGL(k_geometry<double>, g, b, 0, s, gamma, c.edges, c.nE, c.gd.a, c.gd.b, c.gd.t, c.status);
   RC_HIP(hipGetLastError());
   return RC_OK;
 }
@@ -943,7 +969,7 @@ rc_status launch_tpe(const Curve& c, double alpha, double beta, rc_dtype prec, b
   const int band_chunk = (prec == RC_F32 && c.chain) ? c.nchunk : -1;
   hipLaunchKernelGGL(k_tpe_finalize, dim3(cdiv(c.nE, 64)), dim3(256), 0, s, c.part, c.nchunk,
                      (const int*)(c.n_inst > 0 ? c.nch_e : nullptr), band_chunk, c.nE, grad ? 1 : 0,
-                     (const double*)c.gd.a, (const double*)c.gd.t, c.edge_out);
+                     (const double*)c.gd.a, (const double*)c.gd.t, c.edge_out, c.status);
   if (c.obstacle.on) {
     const Obstacle& o = c.obstacle;
     hipLaunchKernelGGL(k_obstacle, dim3(cdiv(c.nE, 256)), dim3(256), 0, s, c.gd.a, c.gd.b, c.gd.t, c.nE, o.c[0],
@@ -951,7 +977,7 @@ rc_status launch_tpe(const Curve& c, double alpha, double beta, rc_dtype prec, b
   }
   if (grad && dE)
     hipLaunchKernelGGL(k_gather_vertex, dim3(cdiv(c.nV, 256)), dim3(256), 0, s, c.edge_out, c.inc_off,
-                       c.inc, c.nV, dE);
+                       c.inc, c.nV, dE, c.status);
   if (energy) sum_edge_slot(c, 0, energy, s);
   RC_HIP(hipGetLastError());
   return RC_OK;
@@ -1039,10 +1065,10 @@ rc_status launch_midpoint(const Curve& c, double alpha, double beta, rc_dtype pr
 
 rc_status finalize_midpoint(const Curve& c, int nparts, double* energy, double* dE, hipStream_t s) {
   hipLaunchKernelGGL(k_mid_finalize, dim3(cdiv(c.nE, 256)), dim3(256), 0, s, c.part, nparts, c.nE,
-                     (const double*)c.gd.a, (const double*)c.gd.t, c.edge_out);
+                     (const double*)c.gd.a, (const double*)c.gd.t, c.edge_out, c.status);
   if (dE)
     hipLaunchKernelGGL(k_gather_vertex, dim3(cdiv(c.nV, 256)), dim3(256), 0, s, c.edge_out, c.inc_off,
-                       c.inc, c.nV, dE);
+                       c.inc, c.nV, dE, c.status);
   if (energy) sum_edge_slot(c, 0, energy, s);
   RC_HIP(hipGetLastError());
   return RC_OK;

@@ -77,10 +77,24 @@ std::vector<Chain> chains_of(const Curve& c);
 // the near-band kernel when the pair kernels run in FP32 (see k_pairs.hip).
 constexpr int kBand = 32;
 
+// Conditions latched into a context's device status word (bitwise OR, read and
+// cleared by rc_sync_status).  The kernels that detect them set their bit with
+// an atomic OR; the host-side solver conditions are kept in a host word of the
+// context and merged when the status is read.
+enum StatusFlag : uint32_t {
+  kFlagInputNonfinite = RC_FLAG_INPUT_NONFINITE,
+  kFlagZeroEdge = RC_FLAG_ZERO_EDGE,
+  kFlagPairOverflow = RC_FLAG_PAIR_OVERFLOW,
+  kFlagResultNonfinite = RC_FLAG_RESULT_NONFINITE,
+};
+__device__ __forceinline__ void latch(unsigned* status, unsigned flag) {
+  if (status) atomicOr(status, flag);
+}
+
 // Optional HIP-event timing of the pair kernels (enabled per context).
 struct KernelTimer {
   bool on = false;
-  std::vector<hipEvent_t> tpe, sob, lowp, asm32, sob64, basm;  // start/stop pairs, in launch order
+  std::vector<hipEvent_t> tpe, sob, lowp, asm32, sob64, basm, bh;  // start/stop pairs, in launch order
   void mark(std::vector<hipEvent_t>& v, hipStream_t s) {
     if (!on) return;
     hipEvent_t e;
@@ -95,6 +109,8 @@ struct KernelTimer {
     for (hipEvent_t e : asm32) hipEventDestroy(e);
     for (hipEvent_t e : sob64) hipEventDestroy(e);
     for (hipEvent_t e : basm) hipEventDestroy(e);
+    for (hipEvent_t e : bh) hipEventDestroy(e);
+    bh.clear();
     sob64.clear();
     basm.clear();
     tpe.clear();
@@ -133,6 +149,7 @@ struct Curve {
   int* chain_edge = nullptr;       // edges in chain order (cinfo.x + position -> edge)
 
   KernelTimer* timer = nullptr;    // set on the finest level when profiling is on
+  unsigned* status = nullptr;      // the context's device status word (not owned); null on coarse levels
 
   int nchunk = 1, src_per_chunk = 0;
   int part_chunks = 0;             // chunks part has room for (the near band uses chunk nchunk)

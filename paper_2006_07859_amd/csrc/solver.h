@@ -148,6 +148,8 @@ struct rc_ctx {
   rc::Dense dense;
   rc::Bvh bvh;
   rc::KernelTimer timer;
+  unsigned* status_dev = nullptr;  // device status word (RC_FLAG_* bits latched by kernels)
+  unsigned status_host = 0;        // RC_FLAG_* bits latched by the host-side solver
   // precision path: the finest level's assembled 16-bit operator; levels
   // 0 .. lowp_levels-1 use their assembled operator in the current solve
   rc::LowpOp lowp;

@@ -1236,6 +1236,7 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
   const double lbar = Ltot / std::max(1, c->nE);
   const Cons& K = c->cons;
   double tau = ls.tau0;
+  bool any_projected = false;  // some trial reached the constraint tolerance
   for (int bt = 0; bt <= ls.max_backtracks; ++bt) {
     vec_trial(gamma, g, c->scal + 16, tau, c->trial, n3, s);
     bool ok = (k == 0);
@@ -1271,6 +1272,7 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
       out->proj_solve_iters += pit;
       vec_axpby(1.0, c->dx, 1.0, c->trial, n3, s);
     }
+    any_projected |= ok;
     if (ok) {
       RC_TRY(load_geometry(c, c->trial));
       RC_TRY(launch_tpe(c->curve, c->alpha, c->beta, c->dtype, false, c->scal + 18, nullptr, s));
@@ -1288,8 +1290,12 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
     }
     tau *= ls.shrink;
   }
-  set_error("line search found no admissible step");
   out->backtracks = ls.max_backtracks;
+  if (!any_projected) {
+    set_error("constraint projection did not reach its tolerance at any step length");
+    return RC_ERR_PROJECTION;
+  }
+  set_error("line search found no admissible step");
   return RC_ERR_LINESEARCH;
 }
 

@@ -63,3 +63,4 @@ def test_argument_validation_without_gpu():
     assert b"alpha" in lib.rc_last_error() or len(lib.rc_last_error()) > 0
     # null context
     assert lib.rc_energy(None, None, None) == 1
+    assert lib.rc_sync_status(None, None) == 1
