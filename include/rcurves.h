@@ -214,6 +214,25 @@ rc_status rc_energy(rc_ctx* ctx, const double* gamma, double* energy);
  * dE: device double [nV][3] (written).  energy may be NULL. */
 rc_status rc_differential(rc_ctx* ctx, const double* gamma, double* energy, double* dE);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): energy and
+ * differential as rc_differential computes them on an RC_F64 context, with no
+ * context and no allocation.  Its workspace (edge geometry, pair partial sums,
+ * per-edge values; about 32 MB) is one static device array that each GPU the
+ * library runs on holds until the process ends.
+ * gamma: device double [n_vertices][3]; edges: DEVICE int32 [n_edges][2]
+ * oriented (i1, i2), every vertex of degree <= 2 (loops and open paths: then
+ * dE is bitwise reproducible; a higher degree gives the same sums in an
+ * unfixed rounding order); energy: device double [1] or NULL; dE: device
+ * double [n_vertices][3], overwritten.  1 <= n_edges <= 16384 and
+ * 2 <= n_vertices <= 1048576, else RC_ERR_ARG; (alpha, beta) as rc_create,
+ * else RC_ERR_PARAM_RANGE.  An edge whose endpoints are out of range or equal
+ * is not read: it makes the energy NaN.  Stream-ordered on `stream`, no
+ * synchronisation.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (other streams, other threads) race. */
+rc_status rc_differential_noalloc(const double* gamma, int32_t n_vertices, const int32_t* edges, int32_t n_edges,
+                                  double alpha, double beta, double* energy, double* dE, rc_stream stream);
+
 /* Y = Abar X with A = B + B0 (eqs. DiscreteHighOrderPart, Sec. 4.2.3,
  * eq. VectorInnerProduct), evaluated matrix-free from gamma in the context's
  * dtype.  X, Y: device double [nV][3]; Y is overwritten. */

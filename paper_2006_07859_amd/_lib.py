@@ -37,6 +37,7 @@ EXPORTED = [
     "rc_batch_sobolev_apply", "rc_mlp_n_params", "rc_mlp_create", "rc_mlp_destroy", "rc_mlp_get", "rc_mlp_set", "rc_mlp_forward",
     "rc_mlp_backward", "rc_mlp_adam", "rc_learned_attach", "rc_learned_levels", "rc_learned_features",
     "rc_learned_scalings", "rc_learned_apply", "rc_learned_train_step", "rc_sync_status",
+    "rc_differential_noalloc",
 ]
 
 RC_FLAG_INPUT_NONFINITE, RC_FLAG_ZERO_EDGE, RC_FLAG_PAIR_OVERFLOW, RC_FLAG_RESULT_NONFINITE = 1, 2, 4, 8
@@ -142,6 +143,7 @@ def load():
         "rc_mlp_adam": (I32, [P, P, C.c_float]),
         "rc_learned_attach": (I32, [P, P]),
         "rc_sync_status": (I32, [P, C.POINTER(Stats)]),
+        "rc_differential_noalloc": (I32, [P, I32, P, I32, D, D, P, P, P]),
         "rc_learned_levels": (I32, [P, I32, P, I32, C.POINTER(I32)]),
         "rc_learned_features": (I32, [P, P, I32, P, P]),
         "rc_learned_scalings": (I32, [P, P, I32, P]),
@@ -207,6 +209,20 @@ def default_ls_opts(**kw):
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+def differential_noalloc(gamma, edges, alpha, beta, energy, dE):
+    """rc_differential_noalloc: FP64 energy and differential with no context and no allocation.
+    gamma, dE: device float64 [nV, 3]; edges: device int32 [nE, 2]; energy: device float64 [1] or None."""
+    import torch
+
+    nV = int(gamma.shape[0])
+    if not isinstance(edges, torch.Tensor) or edges.dtype != torch.int32 or edges.ndim != 2 or edges.shape[1] != 2:
+        raise TypeError("edges must be a device int32 tensor [n_edges, 2]")
+    _check(load().rc_differential_noalloc(_ptr(gamma, (nV, 3), torch.float64, "gamma"), nV,
+                                          _ptr(edges, None, torch.int32, "edges"), int(edges.shape[0]), float(alpha),
+                                          float(beta), _ptr(energy, (1,), torch.float64, "energy"),
+                                          _ptr(dE, (nV, 3), torch.float64, "dE"), _stream()))
 
 
 class Context:
