@@ -29,15 +29,16 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP32 flops per ordered edge pair (four vertex pairs) of the two pair kernels;
-# the transcendental operations (rsqrt, sqrt) are counted separately and not
-# included.  Energy + differential: 280 flops for the gather form whose four
-# vertex pairs share the difference vectors, |T x d|, T.d and r^-beta work (the
-# lower end of its 280-300 estimate).  The (2, 4.5) kernel executes 213 flops
-# and 8 transcendentals per pair (its gfx950 inner loop), reported beside it;
-# evaluating the four vertex pairs independently would take 344.
-FLOPS_PER_PAIR_TPE = 280   # energy + differential, algorithmic
-FLOPS_PER_PAIR_TPE_EXEC = 213  # energy + differential, executed by the (2, 4.5) FP32 kernel
+# FP32 flops of the energy + differential kernel.  For alpha = 2 on loops and
+# paths the kernel evaluates the trapezoid sum regrouped by vertex pair: one
+# pair of vertices (v, w) stands for the four vertex pairs of the four edge
+# pairs at v and w, at 93 flops (32 + 4 FMAs, 18 multiplies, 3 subtractions in
+# its gfx950 inner loop) and 2 transcendentals (rsqrt, sqrt) per vertex pair,
+# and a closed curve has as many vertex pairs as edge pairs.  The edge-pair
+# form it replaces took 280 algorithmic flops per edge pair (213 executed).
+FLOPS_PER_PAIR_TPE = 93    # energy + differential, vertex-pair form (algorithmic = executed)
+FLOPS_PER_PAIR_TPE_EXEC = 93
+FLOPS_PER_EDGE_PAIR = 280  # energy + differential, edge-pair form (other exponents, batches)
 # Operator A = B + B0 applied to 3 right-hand sides: about 100 flops per pair for
 # the gather form; the FP32 kernel executes about 135 and 8 transcendentals per
 # pair, the FP64 one about 190 with its powers from an FP32 estimate and Newton steps.
@@ -288,10 +289,11 @@ def main():
     t_eval = float(np.mean([s["t_eval_ms"] for s in stats])) * 1e-3
     value = P / t_eval
     tpe_avg = tpe_ms / max(tpe_n, 1) * 1e-3
-    roof_tpe = FLOPS_PER_PAIR_TPE * P / tpe_avg / 1e12
+    VP = len(g) * len(g)  # ordered vertex pairs the kernel visits (the near band's masked ones included)
+    roof_tpe = FLOPS_PER_PAIR_TPE * VP / tpe_avg / 1e12
     # the timed kernels of the step (finest level), each against its own roofline
     kernels = [
-        ("k_tpe_pairs<float> (energy+differential)", tpe_ms, tpe_n, FLOPS_PER_PAIR_TPE * P / 1e12, "alu",
+        ("k_vp_pairs<float> (energy+differential, vertex-pair form)", tpe_ms, tpe_n, FLOPS_PER_PAIR_TPE * VP / 1e12, "alu",
          PEAK_FP32_TFLOPS, "TFLOP/s"),
         ("k_sob_pairs<float> (FP32 operator, finest level)", sob_ms, sob_n, FLOPS_PER_PAIR_SOB * P / 1e12, "alu",
          PEAK_FP32_TFLOPS, "TFLOP/s"),
@@ -317,7 +319,8 @@ def main():
     roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roofline["flops_per_pair"] = FLOPS_PER_PAIR_TPE
     roofline["executed_flops_per_pair"] = FLOPS_PER_PAIR_TPE_EXEC
-    roofline["executed_achieved"] = round(FLOPS_PER_PAIR_TPE_EXEC * P / tpe_avg / 1e12, 3)
+    roofline["executed_achieved"] = round(FLOPS_PER_PAIR_TPE_EXEC * VP / tpe_avg / 1e12, 3)
+    roofline["vertex_pairs_per_launch"] = VP
     roofline["executed_frac"] = round(roofline["executed_achieved"] / PEAK_FP32_TFLOPS, 4)
     roofline["executed_frac_nonpacked"] = round(roofline["executed_achieved"] / (PEAK_FP32_TFLOPS / 2), 4)
     out = {
@@ -354,11 +357,11 @@ def main():
         "roofline": roofline,
         "rooflines_timed_kernels": rooflines,
         "roofline_energy_differential": {
-            "kernel": "k_tpe_pairs<float>", "launches": tpe_n, "avg_launch_ms": round(tpe_avg * 1e3, 4),
+            "kernel": "k_vp_pairs<float>", "launches": tpe_n, "avg_launch_ms": round(tpe_avg * 1e3, 4),
             "achieved": round(roof_tpe, 3), "unit": "TFLOP/s", "frac": round(roof_tpe / PEAK_FP32_TFLOPS, 4),
             "pairs_per_s_kernel": P / tpe_avg, "flops_per_pair": FLOPS_PER_PAIR_TPE,
             "executed_flops_per_pair": FLOPS_PER_PAIR_TPE_EXEC,
-            "executed_tflops": round(FLOPS_PER_PAIR_TPE_EXEC * P / tpe_avg / 1e12, 3),
+            "executed_tflops": round(FLOPS_PER_PAIR_TPE_EXEC * VP / tpe_avg / 1e12, 3),
         },
     }
     # the same steps with the plain solver (FP32 matrix-free smoothers), from the same start
@@ -679,7 +682,7 @@ def bench_batch(args):
     asm_bytes = int((sizes * sizes).sum() * 4)  # every FP32 entry once
     asm_avg = asm_ms / max(asm_n, 1) * 1e-3
     asm_gbs = asm_bytes / asm_avg / 1e9
-    achieved = FLOPS_PER_PAIR_TPE * P / tpe_avg / 1e12
+    achieved = FLOPS_PER_EDGE_PAIR * P / tpe_avg / 1e12  # (3, 6): the edge-pair form
     big = int(np.argmax(np.diff(voff)))
     out = {
         "metric": "aggregate edge-pair evals/s (energy+grad, 512-instance batch)",

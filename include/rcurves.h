@@ -205,6 +205,19 @@ rc_status rc_create(int32_t n_vertices, int32_t n_edges, const int32_t* edges_h,
                     rc_ctx** out);
 rc_status rc_destroy(rc_ctx* ctx);
 
+/* Chooses how an RC_F32 context with alpha = 2 on one network of vertex
+ * degree <= 2 (loops and open paths) evaluates the energy and differential:
+ * enable != 0 (the default for such contexts) regroups the trapezoid sum of
+ * eq. DiscreteEnergy by vertex pair (v, w): for alpha = 2,
+ * sum_{I at v, J at w} l_I l_J |T_I x d|^2 = (sum_{I at v} l_I |T_I x d|^2)
+ * (sum_{J at w} l_J) whenever the edges at v and at w are disjoint, so one
+ * pair of vertices replaces four vertex pairs of four edge pairs; pairs of
+ * vertices at most 32 steps apart along a chain are summed in FP64 in the
+ * edge-pair form.  enable = 0 uses the edge-pair form everywhere.  The sums are
+ * the same; the rounding differs.  Other contexts: RC_ERR_UNSUPPORTED for
+ * enable != 0.  Synchronises the stream when enabling. */
+rc_status rc_use_vertex_pairs(rc_ctx* ctx, int32_t enable);
+
 /* Discrete energy (eqs. DiscreteEnergy, DiscreteKernel): the sum over ordered
  * pairs of edges sharing no vertex of l_I l_J * 1/4 sum_{i in I, j in J} k(g_i, g_j, T_I).
  * gamma: device double [nV][3].  energy: device double [1] (written). */

@@ -37,7 +37,7 @@ EXPORTED = [
     "rc_batch_sobolev_apply", "rc_mlp_n_params", "rc_mlp_create", "rc_mlp_destroy", "rc_mlp_get", "rc_mlp_set", "rc_mlp_forward",
     "rc_mlp_backward", "rc_mlp_adam", "rc_learned_attach", "rc_learned_levels", "rc_learned_features",
     "rc_learned_scalings", "rc_learned_apply", "rc_learned_train_step", "rc_sync_status",
-    "rc_differential_noalloc",
+    "rc_differential_noalloc", "rc_use_vertex_pairs",
 ]
 
 RC_FLAG_INPUT_NONFINITE, RC_FLAG_ZERO_EDGE, RC_FLAG_PAIR_OVERFLOW, RC_FLAG_RESULT_NONFINITE = 1, 2, 4, 8
@@ -144,6 +144,7 @@ def load():
         "rc_learned_attach": (I32, [P, P]),
         "rc_sync_status": (I32, [P, C.POINTER(Stats)]),
         "rc_differential_noalloc": (I32, [P, I32, P, I32, D, D, P, P, P]),
+        "rc_use_vertex_pairs": (I32, [P, I32]),
         "rc_learned_levels": (I32, [P, I32, P, I32, C.POINTER(I32)]),
         "rc_learned_features": (I32, [P, P, I32, P, P]),
         "rc_learned_scalings": (I32, [P, P, I32, P]),
@@ -256,6 +257,9 @@ class Context:
 
     def _v(self, t, name):
         return _ptr(t, (self.nV, 3), self._f64, name)
+
+    def rc_use_vertex_pairs(self, enable=True):
+        _check(load().rc_use_vertex_pairs(self.h, 1 if enable else 0))
 
     def rc_energy(self, gamma, energy):
         _check(load().rc_energy(self.h, self._v(gamma, "gamma"), _ptr(energy, (1,), self._f64, "energy")))

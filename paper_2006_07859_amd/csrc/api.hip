@@ -156,6 +156,8 @@ static rc_status create_ctx(int32_t nV, int32_t nE, const int32_t* edges_h, doub
   if (n_inst > 0) {
     RC_TRY(c->curve.set_instances(n_inst, voff_h));
     RC_TRY(batch_alloc(c.get()));
+  } else if (c->curve.chain && alpha == 2.0 && dtype == RC_F32) {
+    RC_TRY(c->curve.enable_vertex_pairs());
   }
   const size_t n3 = 3 * (size_t)nV;
   double** vecs[] = {&c->x,    &c->r,    &c->z,   &c->p,  &c->q,   &c->tmp, &c->tmp2,
@@ -251,6 +253,20 @@ rc_status rc_sync_status(rc_ctx* c, rc_stats* out) {
     out->flags = f;
   }
   return st;
+}
+
+rc_status rc_use_vertex_pairs(rc_ctx* c, int32_t enable) {
+  RC_TRY(check_ctx(c));
+  if (!enable) {
+    c->curve.vp = false;
+    return RC_OK;
+  }
+  if (c->curve.n_inst > 0 || !c->curve.chain || c->alpha != 2.0 || c->dtype != RC_F32) {
+    set_error("rc_use_vertex_pairs: needs an RC_F32 context with alpha = 2 on one network of vertex degree <= 2");
+    return RC_ERR_UNSUPPORTED;
+  }
+  RC_HIP(hipStreamSynchronize(c->stream));
+  return c->curve.enable_vertex_pairs();
 }
 
 rc_status rc_energy(rc_ctx* c, const double* gamma, double* energy) {

@@ -247,12 +247,45 @@ rc_status Curve::build_items(int src_chunk, int blocks_per_cu_) {
   return RC_OK;
 }
 
+rc_status Curve::enable_vertex_pairs() {
+  if (vinfo) {  // buffers kept from an earlier enable
+    vp = true;
+    return RC_OK;
+  }
+  if (!chain || n_inst > 0) {
+    set_error("the vertex-pair form needs a single network of vertex degree <= 2");
+    return RC_ERR_UNSUPPORTED;
+  }
+  std::vector<int4> hv(nV);
+  for (int v = 0; v < nV; ++v) hv[v] = make_int4(-1 - v, 0, 1, 0);  // isolated vertex: a chain of its own
+  std::vector<Chain> chs = chains_of(*this);
+  for (size_t k = 0; k < chs.size(); ++k) {
+    const int m = (int)chs[k].verts.size();
+    for (int p = 0; p < m; ++p) hv[chs[k].verts[p]] = make_int4((int)k, p, m, chs[k].loop ? 1 : 0);
+  }
+  const int tb = (nV + kTile - 1) / kTile;
+  vchunk = std::max(1, std::min(tb, (2048 + tb - 1) / tb));
+  vsrc_per_chunk = (nV + vchunk - 1) / vchunk;
+  RC_TRY(dmalloc(&vinfo, nV));
+  for (int k = 0; k < 3; ++k) RC_TRY(dmalloc(&vg[k], nV));
+  RC_TRY(dmalloc(&vpart, (size_t)vchunk * kVpSlots * nV));
+  RC_TRY(dmalloc(&vout, (size_t)kVpOut * nV));
+  RC_HIP(hipMemcpy(vinfo, hv.data(), sizeof(int4) * nV, hipMemcpyHostToDevice));
+  vp = true;
+  return RC_OK;
+}
+
 void Curve::release() {
   void* ptrs[] = {edges, inc_off, inc, gf.a, gf.b, gf.t, gd.a, gd.b, gd.t,
                   rhs_f[0], rhs_f[1], rhs_d[0], rhs_d[1], part, edge_out, red, cinfo, chain_edge,
-                  inst_voff, inst_eoff, inst_of_edge, inst_of_vertex, items, nch_e, counter};
+                  inst_voff, inst_eoff, inst_of_edge, inst_of_vertex, items, nch_e, counter,
+                  vinfo, vg[0], vg[1], vg[2], vpart, vout};
   for (void* p : ptrs)
     if (p) hipFree(p);
+  vp = false;
+  vinfo = nullptr;
+  vg[0] = vg[1] = vg[2] = nullptr;
+  vpart = vout = nullptr;
   inst_voff = inst_eoff = inst_of_edge = inst_of_vertex = nch_e = counter = nullptr;
   items = nullptr;
   n_inst = n_items = 0;

@@ -65,45 +65,6 @@ __device__ __forceinline__ bool chain_near(int4 ci, int4 cj) {
   return (cj.x == ci.x) & (dd <= kBand);
 }
 
-// Range (min chain, max chain, min position, max position) of the chain
-// coordinates held by the valid threads of a workgroup of kTile threads: each
-// wave reduces with cross-lane exchanges and writes its slot of red; after a
-// barrier, range_of(red) combines the slots.
-__device__ __forceinline__ void wave_range(int4 c, bool valid, int4* red) {
-  int cmin = valid ? c.x : INT_MAX, cmax = valid ? c.x : INT_MIN;
-  int pmin = valid ? c.y : INT_MAX, pmax = valid ? c.y : INT_MIN;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    cmin = min(cmin, __shfl_xor(cmin, o));
-    cmax = max(cmax, __shfl_xor(cmax, o));
-    pmin = min(pmin, __shfl_xor(pmin, o));
-    pmax = max(pmax, __shfl_xor(pmax, o));
-  }
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_int4(cmin, cmax, pmin, pmax);
-}
-
-__device__ __forceinline__ int4 range_of(const int4* red) {
-  int4 r = red[0];
-#pragma unroll
-  for (int w = 1; w < kTile / 64; ++w) {
-    const int4 v = red[w];
-    r = make_int4(min(r.x, v.x), max(r.y, v.y), min(r.z, v.z), max(r.w, v.w));
-  }
-  return r;
-}
-
-// True when no target of range tr is chain-near any source of range sr: the
-// chain ranges are disjoint, or both tiles lie on one chain (length m, a loop
-// when loop != 0) with position intervals more than kBand apart, also around
-// the loop.  Conservative: false whenever the ranges cannot decide.
-__device__ __forceinline__ bool tiles_far(int4 tr, int4 sr, int m, int loop) {
-  if (tr.y < sr.x || sr.y < tr.x) return true;
-  if (tr.x != tr.y || sr.x != sr.y) return false;
-  const int gap = max(sr.z - tr.w, tr.z - sr.w);
-  if (gap <= kBand) return false;
-  return !loop || m - (max(tr.w, sr.w) - min(tr.z, sr.z)) > kBand;
-}
-
 // BAND: the graph is a union of chains and the kernel runs in FP32; pairs
 // that are chain-near (which include every pair sharing a vertex) are left
 // to the FP64 near-band kernel.  Otherwise only pairs sharing a vertex are
@@ -903,6 +864,7 @@ rc_status launch_geometry(const Curve& c, const double* gamma, rc_dtype prec, hi
                        (unsigned*)nullptr);
   // the FP64 copy is always kept: the finalize kernels read l_I and T_I from it
   hipLaunchKernelGGL(k_geometry<double>, g, b, 0, s, gamma, c.edges, c.nE, c.gd.a, c.gd.b, c.gd.t, c.status);
+  if (c.vp && prec == RC_F32) launch_vertex_geometry(c, gamma, s);
   RC_HIP(hipGetLastError());
   return RC_OK;
 }
@@ -958,6 +920,16 @@ static void dispatch_tpe(const Curve& c, const EdgeGeom<R>& g, double alpha, dou
 
 rc_status launch_tpe(const Curve& c, double alpha, double beta, rc_dtype prec, bool grad,
                      double* energy, double* dE, hipStream_t s) {
+  if (c.vp && prec == RC_F32 && alpha == 2.0 && c.n_inst == 0 && !c.obstacle.on) {
+    // alpha = 2 chain graph: the vertex-pair form, its FP64 near band in chunk 0
+    RC_TRY(launch_tpe_vp_pairs(c, beta, grad, s));
+    hipLaunchKernelGGL(k_tpe_finalize, dim3(cdiv(c.nE, 64)), dim3(256), 0, s, c.part, 0, (const int*)nullptr, 0,
+                       c.nE, grad ? 1 : 0, (const double*)c.gd.a, (const double*)c.gd.t, c.edge_out, c.status);
+    RC_TRY(launch_tpe_vp_finish(c, beta, grad, dE, s));
+    if (energy) sum_edge_slot(c, 0, energy, s);
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+  }
   if (prec == RC_F32) {
     if (grad) dispatch_tpe<float, true>(c, c.gf, alpha, beta, s);
     else dispatch_tpe<float, false>(c, c.gf, alpha, beta, s);

@@ -3,11 +3,51 @@
 // accumulation of the tangent-point energy and its derivatives.
 #pragma once
 
+#include <climits>
 #include <type_traits>
 
 #include "rc_internal.h"
 
 namespace rc {
+
+// Range (min chain, max chain, min position, max position) of the chain
+// coordinates held by the valid threads of a workgroup of kTile threads: each
+// wave reduces with cross-lane exchanges and writes its slot of red; after a
+// barrier, range_of(red) combines the slots.
+__device__ __forceinline__ void wave_range(int4 c, bool valid, int4* red) {
+  int cmin = valid ? c.x : INT_MAX, cmax = valid ? c.x : INT_MIN;
+  int pmin = valid ? c.y : INT_MAX, pmax = valid ? c.y : INT_MIN;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    cmin = min(cmin, __shfl_xor(cmin, o));
+    cmax = max(cmax, __shfl_xor(cmax, o));
+    pmin = min(pmin, __shfl_xor(pmin, o));
+    pmax = max(pmax, __shfl_xor(pmax, o));
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_int4(cmin, cmax, pmin, pmax);
+}
+
+__device__ __forceinline__ int4 range_of(const int4* red) {
+  int4 r = red[0];
+#pragma unroll
+  for (int w = 1; w < kTile / 64; ++w) {
+    const int4 v = red[w];
+    r = make_int4(min(r.x, v.x), max(r.y, v.y), min(r.z, v.z), max(r.w, v.w));
+  }
+  return r;
+}
+
+// True when no target of range tr is chain-near any source of range sr: the
+// chain ranges are disjoint, or both tiles lie on one chain (length m, a loop
+// when loop != 0) with position intervals more than kBand apart, also around
+// the loop.  Conservative: false whenever the ranges cannot decide.
+__device__ __forceinline__ bool tiles_far(int4 tr, int4 sr, int m, int loop) {
+  if (tr.y < sr.x || sr.y < tr.x) return true;
+  if (tr.x != tr.y || sr.x != sr.y) return false;
+  const int gap = max(sr.z - tr.w, tr.z - sr.w);
+  if (gap <= kBand) return false;
+  return !loop || m - (max(tr.w, sr.w) - min(tr.z, sr.z)) > kBand;
+}
 
 // ---------------------------------------------------------------------------
 // math helpers: hardware transcendentals in FP32; in FP64 the hardware
@@ -206,12 +246,16 @@ __device__ __forceinline__ void tpe_vertex_pair(
 // the terms differ from the direct ones by the rounding of the coordinates.
 // w = l_J / 4, and 0 for a skipped pair, whose skipv = 1 keeps |d|^2 >= 1
 // (skipv = 0 otherwise; ignored when SKIP is false).  Ht is not accumulated:
-// T.H replaces it after the sum.
-template <typename R, int EC, bool GRAD, bool SKIP>
+// T.H replaces it after the sum.  With MASK4, only the vertex pairs whose bit
+// is set in m4 are summed (bit 0: (a, c), 1: (a, e), 2: (b, c), 3: (b, e));
+// every term of a vertex pair carries its factor r^-beta, so zeroing that
+// factor removes the vertex pair exactly.
+template <typename R, int EC, bool GRAD, bool SKIP, bool MASK4 = false>
 __device__ __forceinline__ void tpe_edge_pair(
     R ax, R ay, R az, R Tx, R Ty, R Tz, R lI, R cx, R cy, R cz, R Ux, R Uy, R Uz, R lJ,
     R w, R skipv, R half_alpha, R half_beta, R beta,
-    R& E, R& S, R& G1x, R& G1y, R& G1z, R& Gt1, R& G2x, R& G2y, R& G2z, R& Gt2, R& Hx, R& Hy, R& Hz) {
+    R& E, R& S, R& G1x, R& G1y, R& G1z, R& Gt1, R& G2x, R& G2y, R& G2z, R& Gt2, R& Hx, R& Hy, R& Hz,
+    int m4 = 15) {
   const R dx = ax - cx, dy = ay - cy, dz = az - cz;  // d(a, c)
   const R wx = Ty * Uz - Tz * Uy, wy = Tz * Ux - Tx * Uz, wz = Tx * Uy - Ty * Ux;  // T x U
   const R tu = Tx * Ux + Ty * Uy + Tz * Uz;
@@ -237,6 +281,12 @@ __device__ __forceinline__ void tpe_edge_pair(
   rb12 *= w;
   rb21 *= w;
   rb22 *= w;
+  if constexpr (MASK4) {
+    rb11 = (m4 & 1) ? rb11 : R(0);
+    rb12 = (m4 & 2) ? rb12 : R(0);
+    rb21 = (m4 & 4) ? rb21 : R(0);
+    rb22 = (m4 & 8) ? rb22 : R(0);
+  }
   R caI1, fI1, caI2, fI2;
   pow_alpha<EC, R>(cI1, half_alpha, caI1, fI1);
   pow_alpha<EC, R>(cI2, half_alpha, caI2, fI2);

@@ -58,6 +58,8 @@ constexpr int kSub = 64;          // sources folded into FP64 accumulators at a 
 constexpr int kTpeSlots = 14;     // energy + differential accumulators
 constexpr int kSobSlots = 8;      // operator accumulators
 constexpr int kMidSlots = 8;      // midpoint energy + differential accumulators
+constexpr int kVpSlots = 17;      // vertex-pair energy + differential accumulators
+constexpr int kVpOut = 12;        // per-vertex finalised values
 
 // Exponent cases compiled as specialisations; anything else takes the
 // general exp2/log2 path.
@@ -148,6 +150,19 @@ struct Curve {
   int4* cinfo = nullptr;           // per edge (chain start, position, chain length, is loop); chain graphs only
   int* chain_edge = nullptr;       // edges in chain order (cinfo.x + position -> edge)
 
+  // Vertex-pair form of the alpha = 2 energy + differential (chain graphs,
+  // FP32; enable_vertex_pairs): per vertex (chain, position, vertex count, is
+  // loop), the FP32 vertex geometry (x_v, Lambda_v), u_0, u_1 (sqrt(l) T of
+  // the vertex's incident edges in incidence order), the partial sums
+  // [vchunk][kVpSlots][nV] and the finalised per-vertex values [nV][kVpOut].
+  bool vp = false;
+  int4* vinfo = nullptr;
+  V4<float>* vg[3] = {nullptr, nullptr, nullptr};
+  double* vpart = nullptr;
+  double* vout = nullptr;
+  int vchunk = 1, vsrc_per_chunk = 0;
+  rc_status enable_vertex_pairs();
+
   KernelTimer* timer = nullptr;    // set on the finest level when profiling is on
   unsigned* status = nullptr;      // the context's device status word (not owned); null on coarse levels
 
@@ -193,6 +208,15 @@ rc_status launch_sobolev(const Curve& c, double alpha, double beta, rc_dtype pre
 // Exact edge-midpoint energy and differential.
 rc_status launch_midpoint(const Curve& c, double alpha, double beta, rc_dtype prec,
                           double* energy, double* dE, hipStream_t s);
+// Vertex-pair form (k_vpairs.hip): per-vertex FP32 geometry from the FP64
+// edge geometry, and the energy (and differential) of an alpha = 2 chain graph
+// in FP32 with the FP64 near band; called by launch_tpe when c.vp is set.
+// The FP32 vertex-pair sums and the FP64 near band (part chunk 0), then,
+// after the band's edge finalize, the vertex finalize, the edge partials and
+// the gather into dE.
+void launch_vertex_geometry(const Curve& c, const double* gamma, hipStream_t s);
+rc_status launch_tpe_vp_pairs(const Curve& c, double beta, bool grad, hipStream_t s);
+rc_status launch_tpe_vp_finish(const Curve& c, double beta, bool grad, double* dE, hipStream_t s);
 // Shared tail of the edge-midpoint kernels: sums nparts chunks of the
 // 10-slot partials, writes energy and dE.
 rc_status finalize_midpoint(const Curve& c, int nparts, double* energy, double* dE, hipStream_t s);

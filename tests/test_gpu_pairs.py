@@ -109,6 +109,47 @@ def test_f32_band_tiles_of_several_chains(lib):
         assert relnorm(host(dE), G_ref) < 1e-4
 
 
+@pytest.mark.parametrize("beta", [4.0, 4.5, 4.8])
+def test_vertex_pair_form_against_edge_pair_form_and_oracle(lib, beta):
+    """The alpha = 2 vertex-pair regrouping (default for FP32 chain graphs) and the edge-pair form, on
+    one network holding a 1,000-edge knot, a 9-edge trefoil and a 5-gon (loops shorter than the near
+    band, summed entirely in FP64), a 300-edge open path and a 5-edge open path, shuffled: both
+    against the oracle at the FP32 tolerances, and against each other.  beta = 4.8 takes the general
+    power path."""
+    from paper_2006_07859_amd import RC_F32
+
+    banner(f"energy+dE f32 vertex-pair vs edge-pair form, (2,{beta})")
+    g1, e1, _ = gen.fourier_knot(1000, seed=7)
+    g2, e2 = gen.trefoil(9, seed=2)
+    g2 = 0.3 * g2 + [5.0, 0.0, 0.0]
+    g3, e3 = gen.regular_ngon(5, radius=0.5)
+    g3 = g3 + [0.0, 5.0, 0.0]
+    t = np.linspace(0.0, 1.0, 301)
+    g4 = np.stack([0.5 * np.cos(5 * t) - 4.0, 0.5 * np.sin(5 * t), 2.0 * t], 1)
+    e4 = np.stack([np.arange(300), np.arange(1, 301)], 1)
+    g5 = np.stack([np.linspace(0, 1, 6), np.full(6, -4.0), 0.2 * np.sin(np.arange(6))], 1)
+    e5 = np.stack([np.arange(5), np.arange(1, 6)], 1)
+    g = gen.round_to_f32(np.concatenate([g1, g2, g3, g4, g5]))
+    e = np.concatenate([e1, e2 + 1000, e3 + 1009, e4 + 1014, e5 + 1315]).astype(np.int32)
+    e = e[np.random.default_rng(3).permutation(len(e))]
+    E_ref, G_ref = tpe.differential(g, e, 2.0, beta)
+    out = {}
+    for vp in (True, False):
+        ctx = ctx_for(lib, g, e, 2.0, beta, RC_F32)
+        ctx.rc_use_vertex_pairs(vp)
+        E, dE, E2 = zeros(1), zeros(len(g), 3), zeros(1)
+        ctx.rc_differential(dev(g), E, dE)
+        ctx.rc_energy(dev(g), E2)
+        assert host(E)[0] == pytest.approx(E_ref, rel=1e-5)
+        assert host(E2)[0] == pytest.approx(host(E)[0], rel=1e-6)  # FP32 rounding of the two kernel variants
+        assert relnorm(host(dE), G_ref) < 1e-4
+        assert ctx.rc_sync_status() == (0, 0)
+        out[vp] = (host(E)[0], host(dE))
+        ctx.close()
+    assert out[True][0] == pytest.approx(out[False][0], rel=2e-6)
+    assert relnorm(out[True][1], out[False][1]) < 5e-5
+
+
 def test_triangle_has_zero_energy(lib):
     from paper_2006_07859_amd import RC_F64
 
