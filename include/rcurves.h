@@ -141,6 +141,11 @@ typedef struct {
   int32_t op_assembled;  /* 1 = the solves' operator is each instance's block of Abar assembled in FP32
                             once per step at gamma (sum of n_i^2 * 4 bytes of device memory, allocated on
                             first use), applied in difference form; 0 = the matrix-free FP32 operator */
+  int32_t refine;        /* rc_batch_gradient only: 0 = one PCG solve to tol judged by its FP32 recurrence;
+                            k > 0 = iterative refinement, k sweeps (at most 20), each a PCG solve to
+                            inner_tol of the FP64 true residual P (dE - Abar g) (FP64 matrix-free
+                            operator) added to g; the reported residual is the final FP64 true one */
+  double inner_tol;      /* relative PCG tolerance of one refinement sweep */
 } rc_batch_opts;
 
 typedef struct {
@@ -152,6 +157,9 @@ typedef struct {
   double proj_tol;       /* relative projection tolerance (times mean edge length) */
   double proj_solve_tol; /* PCG tolerance of the projection increments: C x = -Phi holds exactly
                             whatever it is; it only sets how close x is to the A-norm minimiser */
+  int32_t ccd;           /* 1 = start the search at 2/3 of the first collision time tau_max of the curve
+                            moved along -g/|g| (Sec. 4.4; rc_first_collision_time), sought up to
+                            1.5 tau0, so tau0 without a collision; 0 = start at tau0 */
 } rc_ls_opts;
 
 typedef struct {
@@ -171,6 +179,8 @@ typedef struct {
   double t_search_ms;    /* rc_step: line search with projection */
   int32_t fallback;      /* 1 when the gradient solve fell back to the multigrid preconditioner */
   uint32_t flags;        /* rc_sync_status: the RC_FLAG_* bits latched since the last read */
+  double tau_max;        /* line search with ccd = 1: the first collision time (inf if none within
+                            the searched range) */
 } rc_stats;
 
 /* Waits for the context's stream, reads the RC_FLAG_* bits latched since the
@@ -304,6 +314,16 @@ rc_status rc_line_search_step(rc_ctx* ctx, double* gamma, double energy0, const 
  * line search.  gamma is updated in place.  stats: host, may be NULL. */
 rc_status rc_step(rc_ctx* ctx, double* gamma, const rc_solve_opts* so, const rc_ls_opts* ls,
                   rc_stats* stats);
+
+/* First collision time (Sec. 4.4, time stepping): the smallest t in (0, horizon]
+ * at which two edges sharing no vertex touch when the curve moves as
+ * gamma - t D (every vertex on a straight line), or +inf.  Exact per pair: the
+ * four endpoints are coplanar at a root of the cubic det[p2 - p1, q1 - p1,
+ * q2 - p1](t), and the segments touch there iff their distance is below 1e-9
+ * times the pair's size; pairs moving inside one plane meet where an endpoint
+ * reaches the other segment.  FP64.  gamma, D: device double [nV][3];
+ * t: device double [1]; horizon > 0 (else RC_ERR_ARG).  No synchronisation. */
+rc_status rc_first_collision_time(rc_ctx* ctx, const double* gamma, const double* D, double horizon, double* t);
 
 /* Barnes-Hut energy and differential (App. B.1): a BVH over the tangent-points
  * (T_I, x_I) in R^6 built on the device, admissibility

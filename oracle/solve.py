@@ -35,6 +35,8 @@ __all__ = [
     "saddle_matrix",
     "projected_gradient",
     "projected_gradient_schur",
+    "projected_gradient_structured",
+    "apply_difference_form",
     "projection_increment",
     "projection_increment_transform",
     "project",
@@ -72,6 +74,78 @@ def projected_gradient_schur(A, C, dE):
     lam = np.linalg.solve(S, C @ sla.cho_solve(cf, b))
     g = sla.cho_solve(cf, b - C.T @ lam)
     return g.reshape(-1, 3), lam
+
+
+def apply_difference_form(A, u, block=256):
+    """A u as (A u)_v = sum_w A_vw (u_w - u_v): the increment tables of Sec.
+    4.2.2-4.2.3 give every row of A a zero sum (B and B0 annihilate constants),
+    so this is A u exactly, and for a smooth u it avoids the cancellation
+    between the large diagonal and the off-diagonal terms of the plain product."""
+    A = np.asarray(A)
+    u = np.asarray(u, dtype=np.float64)
+    out = np.zeros_like(u)
+    for s in range(0, A.shape[0], block):
+        rows = slice(s, min(A.shape[0], s + block))
+        diff = u[None, :, :] - u[rows][:, None, :]
+        out[rows] = np.einsum("vw,vwk->vk", A[rows], diff)
+    return out
+
+
+def projected_gradient_structured(A, C, dE, rho=None, refine=4):
+    """Same solution for curves whose 3|V| x 3|V| saddle matrix does not fit: the
+    component structure Abar = kron(A, Id_3) and A 1 = 0 are used instead of
+    forming Abar.
+
+    With ``H0 = A + rho 1 1^T / n`` (symmetric positive definite, since the null
+    space of A is the constants) and ``U = kron(1 / sqrt(n), Id_3)``,
+    ``Abar = kron(H0, Id_3) - rho U U^T``; the unknown ``mu = -rho U^T g`` turns the
+    saddle system into the extended system
+    ``[[Hbar, C^T, U], [C, 0, 0], [U^T, 0, Id_3 / rho]] [g; lam; mu] = [dE; 0; 0]``
+    (``Hbar = kron(H0, Id_3)``), solved through its dense Schur complement of
+    size k + 3, ``(F^T Hbar^-1 F - D) y = F^T Hbar^-1 b - c`` with
+    ``F = [C^T, U]``, ``D = diag(0, Id_3 / rho)``; ``Hbar^-1`` is one Cholesky
+    factor of H0 applied to each coordinate component.  The factorisations are
+    then reused for ``refine`` steps of iterative refinement on the extended
+    system's FP64 residual, with A applied in the difference form
+    (``apply_difference_form``): at large sizes A is ill-conditioned enough
+    (order 2s = 3.5) that one pass, or a residual taken with the plain product,
+    leaves errors far above those of an iterative solver.  C may be dense or
+    scipy.sparse.  Returns (g [V,3], lam).
+    """
+    import scipy.sparse as sp
+
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    if rho is None:
+        rho = float(np.mean(np.diag(A)))
+    cf = sla.cho_factor(A + rho / n, lower=True)
+    Cs = sp.csr_matrix(C)
+    k = Cs.shape[0]
+    U = sp.kron(np.ones((n, 1)) / np.sqrt(n), sp.identity(3), format="csr")
+    F = sp.hstack([Cs.T, U], format="csr")              # 3n x (k + 3)
+    S = np.zeros((k + 3, k + 3))
+    for c in range(3):
+        Fc = F[c::3]                                    # rows of component c: n x (k + 3)
+        S += Fc.T @ sla.cho_solve(cf, Fc.toarray())     # F_c^T H0^-1 F_c
+    S[k:, k:] -= np.eye(3) / rho
+    lu = sla.lu_factor(S, overwrite_a=True)
+    del S
+
+    def solve_ext(b, c):
+        Hb = sla.cho_solve(cf, b)
+        y = sla.lu_solve(lu, F.T @ Hb.ravel() - c)
+        return sla.cho_solve(cf, b - (F @ y).reshape(n, 3)), y
+
+    b = np.asarray(dE, dtype=np.float64).reshape(n, 3)
+    g, y = solve_ext(b, np.zeros(k + 3))
+    for _ in range(refine):
+        lam, mu = y[:k], y[k:]
+        Hg = apply_difference_form(A, g) + (rho / n) * g.sum(0, keepdims=True)
+        r1 = b - Hg - (F @ y).reshape(n, 3)
+        r23 = -(F.T @ g.ravel()) - np.concatenate([np.zeros(k), mu / rho])
+        dg, dy = solve_ext(r1, r23)
+        g, y = g + dg, y + dy
+    return g, y[:k]
 
 
 def projection_increment(A, C, phi):

@@ -37,7 +37,7 @@ EXPORTED = [
     "rc_batch_sobolev_apply", "rc_mlp_n_params", "rc_mlp_create", "rc_mlp_destroy", "rc_mlp_get", "rc_mlp_set", "rc_mlp_forward",
     "rc_mlp_backward", "rc_mlp_adam", "rc_learned_attach", "rc_learned_levels", "rc_learned_features",
     "rc_learned_scalings", "rc_learned_apply", "rc_learned_train_step", "rc_sync_status",
-    "rc_differential_noalloc", "rc_use_vertex_pairs",
+    "rc_differential_noalloc", "rc_use_vertex_pairs", "rc_first_collision_time",
 ]
 
 RC_FLAG_INPUT_NONFINITE, RC_FLAG_ZERO_EDGE, RC_FLAG_PAIR_OVERFLOW, RC_FLAG_RESULT_NONFINITE = 1, 2, 4, 8
@@ -62,13 +62,14 @@ class BatchOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("ls_rounds", C.c_int32), ("proj_iters", C.c_int32),
                 ("proj_max_iter", C.c_int32), ("proj_tol", C.c_double), ("accept_tol", C.c_double),
                 ("c_armijo", C.c_double), ("tau0", C.c_double), ("graph", C.c_int32), ("check_every", C.c_int32),
-                ("coarse", C.c_int32), ("op_assembled", C.c_int32)]
+                ("coarse", C.c_int32), ("op_assembled", C.c_int32), ("refine", C.c_int32),
+                ("inner_tol", C.c_double)]
 
 
 class LsOpts(C.Structure):
     _fields_ = [("c_armijo", C.c_double), ("shrink", C.c_double), ("tau0", C.c_double),
                 ("max_backtracks", C.c_int32), ("max_proj_iter", C.c_int32), ("proj_tol", C.c_double),
-                ("proj_solve_tol", C.c_double)]
+                ("proj_solve_tol", C.c_double), ("ccd", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -76,7 +77,8 @@ class Stats(C.Structure):
                 ("residual", C.c_double), ("tau", C.c_double), ("iterations", C.c_int32),
                 ("proj_solve_iterations", C.c_int32), ("backtracks", C.c_int32), ("proj_iters", C.c_int32),
                 ("status", C.c_int32), ("sweeps", C.c_int32), ("t_eval_ms", C.c_double), ("t_solve_ms", C.c_double),
-                ("t_search_ms", C.c_double), ("fallback", C.c_int32), ("flags", C.c_uint32)]
+                ("t_search_ms", C.c_double), ("fallback", C.c_int32), ("flags", C.c_uint32),
+                ("tau_max", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -145,6 +147,7 @@ def load():
         "rc_sync_status": (I32, [P, C.POINTER(Stats)]),
         "rc_differential_noalloc": (I32, [P, I32, P, I32, D, D, P, P, P]),
         "rc_use_vertex_pairs": (I32, [P, I32]),
+        "rc_first_collision_time": (I32, [P, P, P, D, P]),
         "rc_learned_levels": (I32, [P, I32, P, I32, C.POINTER(I32)]),
         "rc_learned_features": (I32, [P, P, I32, P, P]),
         "rc_learned_scalings": (I32, [P, P, I32, P]),
@@ -260,6 +263,10 @@ class Context:
 
     def rc_use_vertex_pairs(self, enable=True):
         _check(load().rc_use_vertex_pairs(self.h, 1 if enable else 0))
+
+    def rc_first_collision_time(self, gamma, D, horizon, t):
+        _check(load().rc_first_collision_time(self.h, self._v(gamma, "gamma"), self._v(D, "D"), float(horizon),
+                                              _ptr(t, (1,), self._f64, "t")))
 
     def rc_energy(self, gamma, energy):
         _check(load().rc_energy(self.h, self._v(gamma, "gamma"), _ptr(energy, (1,), self._f64, "energy")))

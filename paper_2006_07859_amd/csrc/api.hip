@@ -114,6 +114,7 @@ void rc_default_ls_opts(rc_ls_opts* o) {
   o->max_proj_iter = 10;
   o->proj_tol = 1e-10;
   o->proj_solve_tol = 1e-3;
+  o->ccd = 0;
 }
 
 const char* rc_last_error(void) { return rc::last_error(); }
@@ -197,6 +198,7 @@ rc_status rc_destroy(rc_ctx* c) {
   hipStreamSynchronize(c->stream);
   c->timer.clear();
   c->bvh.release();
+  c->ccd.release();
   c->lowp.release();
   learn_free(c);
   batch_free(c);
@@ -401,9 +403,21 @@ rc_status rc_line_search_step(rc_ctx* c, double* gamma, double energy0, const do
     stats->backtracks = r.backtracks;
     stats->proj_iters = r.proj_iters;
     stats->proj_solve_iterations = r.proj_solve_iters;
+    stats->tau_max = r.tau_max;
     stats->status = st;
   }
   return st;
+}
+
+rc_status rc_first_collision_time(rc_ctx* c, const double* gamma, const double* D, double horizon, double* t) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(check_ptrs({gamma, D, t}));
+  if (!(horizon > 0.0) || !std::isfinite(horizon)) {
+    set_error("rc_first_collision_time: horizon must be positive and finite");
+    return RC_ERR_ARG;
+  }
+  RC_TRY(c->ccd.ensure(c->nE));
+  return launch_first_collision(c->curve, gamma, D, horizon, c->ccd, t, c->stream);
 }
 
 rc_status rc_step(rc_ctx* c, double* gamma, const rc_solve_opts* so, const rc_ls_opts* ls, rc_stats* stats) {
@@ -456,6 +470,7 @@ rc_status rc_step(rc_ctx* c, double* gamma, const rc_solve_opts* so, const rc_ls
     local.backtracks = r.backtracks;
     local.proj_iters = r.proj_iters;
     local.proj_solve_iterations = r.proj_solve_iters;
+    local.tau_max = r.tau_max;
     RC_HIP(hipEventRecord(ev[nev++], s));
   } while (false);
   hipStreamSynchronize(s);
@@ -654,6 +669,8 @@ extern "C" void rc_default_batch_opts(rc_batch_opts* o) {
   o->check_every = 5;
   o->coarse = 1;
   o->op_assembled = 1;
+  o->refine = 0;
+  o->inner_tol = 1e-4;
 }
 
 static rc_status batch_ctx(rc_ctx* c, const char* name) {
@@ -670,7 +687,8 @@ static rc_status batch_opts(const rc_batch_opts* in, rc_batch_opts* o) {
   if (in) *o = *in;
   if (!(o->tol > 0) || o->max_iter < 1 || o->ls_rounds < 1 || o->proj_iters < 0 || o->proj_max_iter < 1 ||
       !(o->proj_tol > 0) || !(o->accept_tol > 0) || !(o->c_armijo > 0) || !(o->tau0 > 0) || o->check_every < 0 ||
-      (o->coarse != 0 && o->coarse != 1) || (o->op_assembled != 0 && o->op_assembled != 1)) {
+      (o->coarse != 0 && o->coarse != 1) || (o->op_assembled != 0 && o->op_assembled != 1) || o->refine < 0 ||
+      o->refine > 20 || !(o->inner_tol > 0) || !(o->inner_tol < 1)) {
     set_error("batch options out of range");
     return RC_ERR_ARG;
   }

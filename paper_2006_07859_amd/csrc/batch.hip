@@ -52,7 +52,7 @@ static rc_status balloc(T** p, size_t n) {
 }
 
 // scalar slots
-enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_RES, S_ACT, S_ITS };
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_RES, S_ACT, S_ITS, S_PB, S_ITA };
 enum { L_E0 = 0, L_E1, L_SLOPE, L_TAU, L_DONE, L_GN, L_PHI, L_TAUACC, L_BT, L_SCALE, L_RES, L_ITS };
 
 // ---------------------------------------------------------------------------
@@ -1148,6 +1148,24 @@ __global__ void k_b_pcg_beta(double* __restrict__ sc, int n_inst, double tol, in
   S[S_RZ] = rzn;
 }
 
+// Refinement bookkeeping: its_total += its of the sweep just solved.
+__global__ void k_b_acc_its(double* __restrict__ sc, int n_inst, int first) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  double* S = sc + (size_t)i * kBatchScal;
+  S[S_ITA] = (first ? 0.0 : S[S_ITA]) + S[S_ITS];
+}
+
+// After the last sweep: the FP64 true relative residual sqrt(<Pr, Pr> / <Pb, Pb>)
+// (S_RR and S_PB) and the iterations of all sweeps.
+__global__ void k_b_true_res(double* __restrict__ sc, int n_inst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  double* S = sc + (size_t)i * kBatchScal;
+  S[S_RES] = S[S_PB] > 0.0 ? sqrt(fmax(S[S_RR], 0.0) / S[S_PB]) : 0.0;
+  S[S_ITS] = S[S_ITA];
+}
+
 // p = z + beta p (active instances).
 __global__ void k_b_pupd(const int* __restrict__ inst_of_vertex, const double* __restrict__ sc, int nV,
                          const double* __restrict__ z, double* __restrict__ p) {
@@ -1712,7 +1730,39 @@ rc_status batch_gradient(rc_ctx* c, const double* gamma, const double* dE, doubl
   c->batch.use_coarse = c->batch.coarse && o.coarse != 0;
   RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));
   RC_TRY(b_prepare(c));
-  return b_pcg(c, dE, g, o.tol, o.max_iter, o.check_every, nullptr);
+  if (o.refine <= 0) return b_pcg(c, dE, g, o.tol, o.max_iter, o.check_every, nullptr);
+  // Iterative refinement (Sec. 4.3.1 per instance, as the single-network solver):
+  // every sweep solves P Abar P d = P (dE - Abar g) with the FP32 operator to
+  // inner_tol and adds d to g; the residual that judges it is the FP64
+  // matrix-free operator's.
+  Batch& B = c->batch;
+  hipStream_t s = c->stream;
+  const int n3 = 3 * c->nV;
+  const dim3 gv(cdiv(n3, 256)), gi(cdiv(B.n_inst, 64)), bi(64), bv(256);
+  const int* vo = c->curve.inst_voff;
+  hipLaunchKernelGGL(k_b_fill, gv, bv, 0, s, g, (size_t)n3, 0.0);
+  b_project(c, dE, B.t);
+  hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.t, B.t, vo, B.sc, kBatchScal, (int)S_PB);
+  for (int sw = 0; sw < o.refine; ++sw) {
+    if (sw == 0) {
+      vec_copy(dE, B.b, n3, s);
+    } else {
+      RC_TRY(launch_sobolev(c->curve, c->alpha, c->beta, RC_F64, g, B.t, nullptr, s));
+      vec_copy(dE, B.b, n3, s);
+      vec_axpby(-1.0, B.t, 1.0, B.b, n3, s);
+    }
+    RC_TRY(b_pcg(c, B.b, B.x, o.inner_tol, o.max_iter, o.check_every, nullptr));
+    hipLaunchKernelGGL(k_b_acc_its, gi, bi, 0, s, B.sc, B.n_inst, sw == 0 ? 1 : 0);
+    vec_axpby(1.0, B.x, 1.0, g, n3, s);
+  }
+  RC_TRY(launch_sobolev(c->curve, c->alpha, c->beta, RC_F64, g, B.t, nullptr, s));
+  vec_copy(dE, B.b, n3, s);
+  vec_axpby(-1.0, B.t, 1.0, B.b, n3, s);
+  b_project(c, B.b, B.b);
+  hipLaunchKernelGGL(k_b_dot, dim3(B.n_inst), bv, 0, s, B.b, B.b, vo, B.sc, kBatchScal, (int)S_RR);
+  hipLaunchKernelGGL(k_b_true_res, gi, bi, 0, s, B.sc, B.n_inst);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
 }
 
 // The whole step on the context stream, without host synchronisation when

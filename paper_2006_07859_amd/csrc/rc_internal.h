@@ -208,6 +208,22 @@ rc_status launch_sobolev(const Curve& c, double alpha, double beta, rc_dtype pre
 // Exact edge-midpoint energy and differential.
 rc_status launch_midpoint(const Curve& c, double alpha, double beta, rc_dtype prec,
                           double* energy, double* dE, hipStream_t s);
+// First collision time (k_ccd.hip): per-edge FP64 endpoints and velocities,
+// FP32 swept boxes and the 64-bit minimum.
+struct CcdBuffers {
+  V4<double>*p1 = nullptr, *p2 = nullptr, *w1 = nullptr, *w2 = nullptr;
+  float4 *lo = nullptr, *hi = nullptr;
+  unsigned long long* bits = nullptr;
+  double* t = nullptr;
+  int nE = 0;
+  rc_status ensure(int nE_);
+  void release();
+};
+// t_out (device) = the first t in (0, T] at which two edges sharing no vertex
+// of gamma - t D touch, or +inf.
+rc_status launch_first_collision(const Curve& c, const double* gamma, const double* D, double T, CcdBuffers& buf,
+                                 double* t_out, hipStream_t s);
+
 // Vertex-pair form (k_vpairs.hip): per-vertex FP32 geometry from the FP64
 // edge geometry, and the energy (and differential) of an alpha = 2 chain graph
 // in FP32 with the FP64 near band; called by launch_tpe when c.vp is set.

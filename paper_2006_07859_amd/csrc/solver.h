@@ -147,6 +147,7 @@ struct rc_ctx {
   // dense direct path on the finest level
   rc::Dense dense;
   rc::Bvh bvh;
+  rc::CcdBuffers ccd;
   rc::KernelTimer timer;
   unsigned* status_dev = nullptr;  // device status word (RC_FLAG_* bits latched by kernels)
   unsigned status_host = 0;        // RC_FLAG_* bits latched by the host-side solver
@@ -196,7 +197,7 @@ rc_status solve_gradient(rc_ctx* c, const double* gamma, const double* rhs, doub
 rc_status solve_prepared(rc_ctx* c, const double* rhs, double* out, const rc_solve_opts& o, int* iters, double* res);
 
 struct LsResult {
-  double tau = 0.0, E1 = 0.0;
+  double tau = 0.0, E1 = 0.0, tau_max = 0.0;
   int backtracks = 0, proj_iters = 0, proj_solve_iters = 0;
 };
 rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, const double* g, const rc_ls_opts& ls,

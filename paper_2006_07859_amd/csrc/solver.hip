@@ -1236,6 +1236,18 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
   const double lbar = Ltot / std::max(1, c->nE);
   const Cons& K = c->cons;
   double tau = ls.tau0;
+  if (ls.ccd) {
+    // Sec. 4.4: start at 2/3 of the first collision time tau_max of gamma - tau g/|g|, sought
+    // up to 1.5 tau0 (so that without a collision the search starts at tau0); any length below
+    // tau_max moves the curve without a self-intersection
+    const double gn = std::sqrt(h[0]);
+    RC_TRY(c->ccd.ensure(c->nE));
+    RC_TRY(launch_first_collision(c->curve, gamma, g, 1.5 * ls.tau0 / gn, c->ccd, c->ccd.t, s));
+    double tc;
+    RC_TRY(fetch(c, c->ccd.t, &tc, 1));
+    out->tau_max = std::isfinite(tc) ? tc * gn : INFINITY;
+    tau = (2.0 / 3.0) * std::min(out->tau_max, 1.5 * ls.tau0);
+  }
   bool any_projected = false;  // some trial reached the constraint tolerance
   for (int bt = 0; bt <= ls.max_backtracks; ++bt) {
     vec_trial(gamma, g, c->scal + 16, tau, c->trial, n3, s);

@@ -135,8 +135,9 @@ def test_gradient_matches_oracle(lib, coarse, op):
     dE = zeros(len(g), 3)
     b.rc_batch_energies(gam, En, dE)
     out = zeros(len(g), 3)
+    # iterative refinement: FP32-operator PCG sweeps to 1e-4 on the FP64 matrix-free true residual
     b.rc_batch_gradient(gam, dE, out, default_batch_opts(tol=1e-7, max_iter=400, check_every=10, coarse=coarse,
-                                                                 op_assembled=op))
+                                                                 op_assembled=op, refine=3, inner_tol=1e-4))
     its, res = b.rc_batch_pcg_state()
     print(f"  iterations {its.astype(int).tolist()} residuals {np.max(res):.1e}")
     out = host(out)
@@ -152,8 +153,8 @@ def test_gradient_matches_oracle(lib, coarse, op):
         err = gi_out.ravel() - g_ref.ravel()
         aerr = np.sqrt(err @ Ab @ err) / np.sqrt(g_ref.ravel() @ Ab @ g_ref.ravel())
         print(f"  instance {i}: n={len(gi)} loops={len(loops)} rel {relnorm(gi_out, g_ref):.2e} A-norm {aerr:.2e}")
-        assert res[i] < 1e-7
-        assert aerr < 3e-4
+        assert res[i] < 1e-7  # the final FP64 true residual
+        assert aerr < 1e-4 and relnorm(gi_out, g_ref) < 1e-4
         assert np.abs(C @ gi_out.ravel()).max() < 1e-8 * np.abs(gi_out).max()
     b.close()
 

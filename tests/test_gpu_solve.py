@@ -115,6 +115,37 @@ def test_pcg_multigrid(lib, mask):
     assert np.sqrt(err @ Ab @ err) / np.sqrt(g_ref.ravel() @ Ab @ g_ref.ravel()) < 1e-4
 
 
+def test_bench_solver_options_match_oracle(lib):
+    """The projected gradient with exactly the options the benchmark's step uses (multigrid PCG to a
+    1e-6 FP64 residual, the Krylov recurrence on the assembled FP32 block refined by FP64 matrix-free
+    true residuals every 1e-3, BF16 assembled blocks as the smoothers' operators on levels of >= 512
+    vertices, Chebyshev degree 2, coarsest level 256) on a 2,048-edge knot with barycenter and
+    edge-length constraints, against the oracle's dense saddle solve (eq. GradientSaddlePointProblem):
+    normwise and A-norm error within the FP32 bound 1e-4 of the projected gradient."""
+    from paper_2006_07859_amd import RC_F32, RC_SOLVE_PCG_MG, default_solve_opts
+
+    n = 2048
+    banner(f"bench solver options vs oracle, fourier{n} barycenter+edge lengths")
+    g, e, _ = gen.fourier_knot(n, seed=5)
+    g = gen.round_to_f32(g)
+    refs, E, dE, A, phi, C = oracle_system(g, e, 2.0, 4.5, BARY | EDGE)
+    g_ref, _ = solve.projected_gradient(A, C, dE)
+    ctx = make(lib, g, e, 2.0, 4.5, RC_F32, BARY | EDGE)
+    so = default_solve_opts(solver=RC_SOLVE_PCG_MG, tol=1e-6, mg_min_vertices=256, cheb_degree=2, op_f64=1,
+                            lowp=1, lowp_band=16, lowp_min_vertices=512, lowp_outer=1, inner_tol=1e-3)
+    out = zeros(n, 3)
+    st = ctx.rc_sobolev_gradient(dev(g), dev(dE), out, so)
+    assert st["residual"] < 1e-6 and st["sweeps"] >= 1
+    Ab = np.kron(A, np.eye(3))
+    err = host(out).ravel() - g_ref.ravel()
+    a_err = np.sqrt(err @ Ab @ err) / np.sqrt(g_ref.ravel() @ Ab @ g_ref.ravel())
+    n_err = relnorm(host(out), g_ref)
+    print(f"  iterations {st['iterations']} sweeps {st['sweeps']} residual {st['residual']:.2e} "
+          f"normwise {n_err:.2e} A-norm {a_err:.2e}")
+    assert n_err < 1e-4 and a_err < 1e-4
+    assert np.abs(C @ host(out).ravel()).max() < 1e-8 * np.abs(host(out)).max()
+
+
 def test_step_dense_matches_oracle(lib):
     from paper_2006_07859_amd import RC_F64, RC_SOLVE_DENSE, default_solve_opts
 

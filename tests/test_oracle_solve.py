@@ -163,3 +163,22 @@ def test_loop_length_step_restores_every_loop():
     assert np.abs(phi[3:]).max() <= 1e-10 * refs[3].max()
     assert np.abs(phi[:3]).max() <= 1e-10 * refs[1] * refs[2].mean()
     assert np.allclose(cons.loop_lengths(new, e), refs[3], rtol=1e-10)
+
+
+@pytest.mark.parametrize("mask", MASKS)
+def test_structured_route_and_sparse_jacobian(mask):
+    # the structured solve used for curves too large for the dense saddle matrix
+    g, e, refs, E, dE, A, phi, C = setup(n=60, mask=mask)
+    Cs = cons.jacobian_sparse(g, e, mask, refs[0])
+    assert np.abs(Cs.toarray() - C).max() == 0.0
+    gt, lam = solve.projected_gradient(A, C, dE)
+    for rho in (None, 1e-3 * np.abs(A).max()):
+        gs, lams = solve.projected_gradient_structured(A, Cs, dE, rho=rho)
+        assert np.abs(gs - gt).max() < 1e-10 * np.abs(gt).max()
+        assert np.abs(lams - lam).max() < 1e-8 * (np.abs(lam).max() + 1)
+
+
+def test_difference_form_product():
+    g, e, refs, E, dE, A, phi, C = setup(n=50)
+    u = np.random.default_rng(4).normal(size=(50, 3))
+    assert np.allclose(solve.apply_difference_form(A, u, block=7), A @ u, rtol=1e-12, atol=1e-12 * np.abs(A @ u).max())
