@@ -325,6 +325,33 @@ rc_status rc_step(rc_ctx* ctx, double* gamma, const rc_solve_opts* so, const rc_
  * t: device double [1]; horizon > 0 (else RC_ERR_ARG).  No synchronisation. */
 rc_status rc_first_collision_time(rc_ctx* ctx, const double* gamma, const double* D, double horizon, double* t);
 
+/* Block cluster tree (App. B.2): builds a BVH over the tangent-points of gamma
+ * (leaves of at most leaf_size <= 64 edges, the builder of rc_bh_differential)
+ * and splits the block (root, root) recursively into blocks (T, S) of BVH
+ * nodes; a block is a leaf when it is admissible (eq. BCTAdmissibilityTest:
+ * max(r_x^T, r_x^S) < theta |c_T - c_S| and max(r_T^T, r_T^S) < theta) or
+ * when both nodes are BVH leaves, otherwise its internal node(s) are split.
+ * theta > 0, 1 <= leaf_size <= 64, else RC_ERR_ARG.  Synchronises (the block
+ * lists are formed on the host from the node data).  The tree is kept until
+ * the next build. */
+rc_status rc_bct_build(rc_ctx* ctx, const double* gamma, double theta, int32_t leaf_size);
+
+/* Counts of the last tree: stats_h (host int64[4]) = BVH nodes, admissible
+ * blocks, inadmissible leaf blocks, edge pairs summed directly in them. */
+rc_status rc_bct_stats(rc_ctx* ctx, int64_t* stats_h);
+
+/* Y = A^ X: the 0th-order hierarchical product (App. B.2) with A = B + B0 in
+ * its kernel-matrix form (App. B.3.4, eqs. LowOrderDecomposition /
+ * LowOrderKernel, and the high-order analogue with k_{0, 2 sigma + 1} and the
+ * difference operator D), the kernel matrices sampled at edge midpoints with
+ * the pairs sharing a vertex left out.  Admissible blocks are the rank-1
+ * blocks L_T k(p_T, p_S) L_S^T with the nodes' tangent-points (centre, mean
+ * tangent) and edge-length vectors; leaf blocks are summed exactly.  FP64
+ * sums, symmetric for any theta, A^ 1 = 0 exactly; as theta -> 0 it is the
+ * kernel-matrix form exactly.  gamma must be the curve of the last
+ * rc_bct_build (its tree is used); X, Y: device double [nV][3]. */
+rc_status rc_sobolev_apply_bct(rc_ctx* ctx, const double* gamma, const double* X, double* Y);
+
 /* Barnes-Hut energy and differential (App. B.1): a BVH over the tangent-points
  * (T_I, x_I) in R^6 built on the device, admissibility
  * r_x < theta |x_I - xbar_B| and r_T < theta (eq. BarnesHutCondition), far

@@ -37,7 +37,8 @@ EXPORTED = [
     "rc_batch_sobolev_apply", "rc_mlp_n_params", "rc_mlp_create", "rc_mlp_destroy", "rc_mlp_get", "rc_mlp_set", "rc_mlp_forward",
     "rc_mlp_backward", "rc_mlp_adam", "rc_learned_attach", "rc_learned_levels", "rc_learned_features",
     "rc_learned_scalings", "rc_learned_apply", "rc_learned_train_step", "rc_sync_status",
-    "rc_differential_noalloc", "rc_use_vertex_pairs", "rc_first_collision_time",
+    "rc_differential_noalloc", "rc_use_vertex_pairs", "rc_first_collision_time", "rc_bct_build", "rc_bct_stats",
+    "rc_sobolev_apply_bct",
 ]
 
 RC_FLAG_INPUT_NONFINITE, RC_FLAG_ZERO_EDGE, RC_FLAG_PAIR_OVERFLOW, RC_FLAG_RESULT_NONFINITE = 1, 2, 4, 8
@@ -148,6 +149,9 @@ def load():
         "rc_differential_noalloc": (I32, [P, I32, P, I32, D, D, P, P, P]),
         "rc_use_vertex_pairs": (I32, [P, I32]),
         "rc_first_collision_time": (I32, [P, P, P, D, P]),
+        "rc_bct_build": (I32, [P, P, D, I32]),
+        "rc_bct_stats": (I32, [P, C.POINTER(C.c_int64)]),
+        "rc_sobolev_apply_bct": (I32, [P, P, P, P]),
         "rc_learned_levels": (I32, [P, I32, P, I32, C.POINTER(I32)]),
         "rc_learned_features": (I32, [P, P, I32, P, P]),
         "rc_learned_scalings": (I32, [P, P, I32, P]),
@@ -263,6 +267,17 @@ class Context:
 
     def rc_use_vertex_pairs(self, enable=True):
         _check(load().rc_use_vertex_pairs(self.h, 1 if enable else 0))
+
+    def rc_bct_build(self, gamma, theta, leaf_size=32):
+        _check(load().rc_bct_build(self.h, self._v(gamma, "gamma"), float(theta), int(leaf_size)))
+
+    def rc_bct_stats(self):
+        out = (C.c_int64 * 4)()
+        _check(load().rc_bct_stats(self.h, out))
+        return {"nodes": out[0], "far_blocks": out[1], "near_blocks": out[2], "near_pairs": out[3]}
+
+    def rc_sobolev_apply_bct(self, gamma, X, Y):
+        _check(load().rc_sobolev_apply_bct(self.h, self._v(gamma, "gamma"), self._v(X, "X"), self._v(Y, "Y")))
 
     def rc_first_collision_time(self, gamma, D, horizon, t):
         _check(load().rc_first_collision_time(self.h, self._v(gamma, "gamma"), self._v(D, "D"), float(horizon),

@@ -199,6 +199,8 @@ rc_status rc_destroy(rc_ctx* c) {
   c->timer.clear();
   c->bvh.release();
   c->ccd.release();
+  c->bct.release();
+  c->bct_bvh.release();
   c->lowp.release();
   learn_free(c);
   batch_free(c);
@@ -407,6 +409,40 @@ rc_status rc_line_search_step(rc_ctx* c, double* gamma, double energy0, const do
     stats->status = st;
   }
   return st;
+}
+
+rc_status rc_bct_build(rc_ctx* c, const double* gamma, double theta, int32_t leaf_size) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_bct_build"));
+  RC_TRY(check_ptrs({gamma}));
+  if (!(theta > 0.0) || !std::isfinite(theta) || leaf_size < 1 || leaf_size > 64) {
+    set_error("rc_bct_build: need theta > 0 and 1 <= leaf_size <= 64");
+    return RC_ERR_ARG;
+  }
+  RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));
+  return build_bct(c->curve, c->bct_bvh, c->bct, theta, leaf_size, c->stream);
+}
+
+rc_status rc_bct_stats(rc_ctx* c, int64_t* stats_h) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(check_ptrs({stats_h}));
+  if (!c->bct.ready) {
+    set_error("rc_bct_stats: no block cluster tree built");
+    return RC_ERR_ARG;
+  }
+  stats_h[0] = c->bct.n_nodes;
+  stats_h[1] = c->bct.n_far;
+  stats_h[2] = c->bct.n_near;
+  stats_h[3] = c->bct.near_pairs;
+  return RC_OK;
+}
+
+rc_status rc_sobolev_apply_bct(rc_ctx* c, const double* gamma, const double* X, double* Y) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_sobolev_apply_bct"));
+  RC_TRY(check_ptrs({gamma, X, Y}));
+  RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));
+  return launch_bct_apply(c->curve, c->bct_bvh, c->bct, c->alpha, c->beta, X, Y, c->stream);
 }
 
 rc_status rc_first_collision_time(rc_ctx* c, const double* gamma, const double* D, double horizon, double* t) {

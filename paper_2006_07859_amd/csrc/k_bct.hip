@@ -1,0 +1,382 @@
+// Block cluster tree and the 0th-order hierarchical product with the Sobolev
+// operator in its kernel-matrix form (App. B.2, App. B.3.4).
+//
+// A = B + B0 written with edge-by-edge kernel matrices (eqs.
+// LowOrderDecomposition, LowOrderKernel):
+//   B0 u = E^T (diag(K 1) - K) E u,  K_IJ = (k_{2,2s'}(x_I, x_J, T_I) + k_{2,2s'}(x_J, x_I, T_J)) l_I l_J,
+//   B u  = D^T (diag(H 1) - H) D u,  H_IJ = 2 |x_I - x_J|^-(2 sigma + 1) l_I l_J,
+// with 2s' = 2 sigma + 5, E the vertex-to-edge average, D the edge
+// derivative (D u)_I = (u_i2 - u_i1) / l_I T_I, pairs sharing a vertex left
+// out.  The products K psi and H psi are approximated on a block cluster tree:
+// blocks (T, S) of BVH nodes, split recursively from (root, root); a block is
+// a leaf when it is admissible (eq. BCTAdmissibilityTest:
+// max(r_x^T, r_x^S) < theta |c_T - c_S| and max(r_T^T, r_T^S) < theta) or when
+// both nodes are BVH leaves; otherwise the larger of the two internal nodes
+// (both when both are internal) is split.  An admissible block is the rank-1
+// block L_T k(p_T, p_S) L_S^T with the nodes' tangent-points p = (c, Tbar) and
+// edge-length vectors L; an inadmissible leaf block is summed exactly, in
+// FP64, over its edge pairs.  The condition and the kernels are symmetric in
+// (T, S), so the approximate matrices are symmetric.
+//
+// Product (all sums in FP64, in fixed orders): per-edge right-hand sides
+// psi_J = l_J (1, (E u)_J, s_J^c T_J) (13 values, s^c = (u^c_j2 - u^c_j1) / l_J),
+// per-node sums Psi_S (contiguous ranges of the BVH permutation), per target
+// node the admissible blocks' Phi_T = sum_S k(p_T, p_S) Psi_S, pushed down to
+// every edge through its ancestors, the exact near blocks per target leaf,
+// then the diagonal and off-diagonal parts combined and gathered to vertices.
+
+#include <algorithm>
+#include <vector>
+
+#include "rc_internal.h"
+
+namespace rc {
+
+static inline int bct_cdiv(int a, int b) { return (a + b - 1) / b; }
+
+constexpr int kPsi = 13;   // 1, E u (3), s^c T (9); times l_J
+constexpr int kPhi = 14;   // K: 1, E u (3); H: 1, s^c T (9)
+
+// Per edge J at BVH position p: psi[p][0..12].
+__global__ void k_bct_rhs(const double* __restrict__ X, const int2* __restrict__ edges,
+                          const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GT,
+                          const int* __restrict__ perm, int nE, double* __restrict__ psi) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nE) return;
+  const int J = perm[p];
+  const int2 e = edges[J];
+  const double l = GA[J].w;
+  const V4<double> t = GT[J];
+  double* o = psi + (size_t)kPsi * p;
+  o[0] = l;
+  for (int c = 0; c < 3; ++c) {
+    const double a = X[3 * e.x + c], b = X[3 * e.y + c];
+    o[1 + c] = l * 0.5 * (a + b);
+    const double sl = (b - a);  // l * s^c
+    o[4 + 3 * c] = sl * t.x;
+    o[5 + 3 * c] = sl * t.y;
+    o[6 + 3 * c] = sl * t.z;
+  }
+}
+
+// Psi_S = sum of psi over the node's range; one workgroup per node.
+__global__ __launch_bounds__(256) void k_bct_node_sums(const int4* __restrict__ node, const double* __restrict__ psi,
+                                                       double* __restrict__ Psi) {
+  __shared__ double sm[kPsi][256];
+  const int4 nd = node[blockIdx.x];
+  double a[kPsi];
+  for (int k = 0; k < kPsi; ++k) a[k] = 0.0;
+  for (int i = threadIdx.x; i < nd.y; i += 256)
+    for (int k = 0; k < kPsi; ++k) a[k] += psi[(size_t)kPsi * (nd.x + i) + k];
+  for (int k = 0; k < kPsi; ++k) sm[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < kPsi; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < kPsi) Psi[(size_t)kPsi * blockIdx.x + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+// The two kernels between tangent-points (x, T) and (y, U), d = x - y:
+// klo = (|T x d|^2 + |U x d|^2) |d|^-(2 sigma + 5), khi = 2 |d|^-(2 sigma + 1).
+__device__ __forceinline__ void bct_kernels(double dx, double dy, double dz, double tx, double ty, double tz,
+                                            double ux, double uy, double uz, double half_expo, double& klo,
+                                            double& khi) {
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double cx = ty * dz - tz * dy, cy = tz * dx - tx * dz, cz = tx * dy - ty * dx;
+  const double ex = uy * dz - uz * dy, ey = uz * dx - ux * dz, ez = ux * dy - uy * dx;
+  const double p = pow(r2, -half_expo);  // |d|^-(2 sigma + 1)
+  khi = 2.0 * p;
+  klo = (cx * cx + cy * cy + cz * cz + ex * ex + ey * ey + ez * ez) * p / (r2 * r2);
+}
+
+// Phi_T = sum over the admissible blocks (T, S) of klo(T, S) (Psi_S[0..3]) and
+// khi(T, S) (Psi_S[0], Psi_S[4..12]); one thread per node, blocks in list order.
+__global__ void k_bct_far(const int* __restrict__ far_off, const int* __restrict__ far_src,
+                          const float4* __restrict__ na, const float4* __restrict__ nb, const double* __restrict__ Psi,
+                          int n_nodes, double half_expo, double* __restrict__ Phi) {
+  const int T = blockIdx.x * blockDim.x + threadIdx.x;
+  if (T >= n_nodes) return;
+  double a[kPhi];
+  for (int k = 0; k < kPhi; ++k) a[k] = 0.0;
+  const float4 ct = na[T], tt = nb[T];
+  for (int q = far_off[T]; q < far_off[T + 1]; ++q) {
+    const int S = far_src[q];
+    const float4 cs = na[S], ts = nb[S];
+    double klo, khi;
+    bct_kernels((double)ct.x - cs.x, (double)ct.y - cs.y, (double)ct.z - cs.z, tt.x, tt.y, tt.z, ts.x, ts.y, ts.z,
+                half_expo, klo, khi);
+    const double* P = Psi + (size_t)kPsi * S;
+    for (int k = 0; k < 4; ++k) a[k] += klo * P[k];
+    a[4] += khi * P[0];
+    for (int k = 0; k < 9; ++k) a[5 + k] += khi * P[4 + k];
+  }
+  for (int k = 0; k < kPhi; ++k) Phi[(size_t)kPhi * T + k] = a[k];
+}
+
+// phi[p] = l_J (sum of Phi over the ancestors of position p, root included).
+__global__ void k_bct_down(const int4* __restrict__ node, const double* __restrict__ Phi,
+                           const V4<double>* __restrict__ GA, const int* __restrict__ perm, int nE,
+                           double* __restrict__ phi) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nE) return;
+  double a[kPhi];
+  for (int k = 0; k < kPhi; ++k) a[k] = 0.0;
+  int B = 0;
+  while (true) {
+    for (int k = 0; k < kPhi; ++k) a[k] += Phi[(size_t)kPhi * B + k];
+    const int4 nd = node[B];
+    if (nd.z < 0) break;
+    const int4 left = node[nd.z];
+    B = (p < left.x + left.y) ? nd.z : nd.z + 1;
+  }
+  const double l = GA[perm[p]].w;
+  for (int k = 0; k < kPhi; ++k) phi[(size_t)kPhi * p + k] = l * a[k];
+}
+
+// Exact near blocks: one workgroup of 64 per target leaf T, a thread per edge
+// of T; every near source leaf S of T in list order, its edges staged in LDS.
+__global__ __launch_bounds__(64) void k_bct_near(const int* __restrict__ near_off, const int* __restrict__ near_src,
+                                                 const int* __restrict__ leaf_node, const int4* __restrict__ node,
+                                                 const int* __restrict__ perm, const int2* __restrict__ edges,
+                                                 const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB,
+                                                 const V4<double>* __restrict__ GT, const double* __restrict__ psi,
+                                                 double half_expo, double* __restrict__ phi) {
+  __shared__ double sx[64][3], st[64][3], sp[64][kPsi];
+  __shared__ int2 se[64];
+  const int Tn = leaf_node[blockIdx.x];
+  const int4 tn = node[Tn];
+  const int tid = threadIdx.x;
+  const bool act = tid < tn.y;
+  const int p = tn.x + (act ? tid : 0);
+  const int I = perm[p];
+  const V4<double> a = GA[I], b = GB[I], t = GT[I];
+  const double x0 = 0.5 * (a.x + b.x), x1 = 0.5 * (a.y + b.y), x2 = 0.5 * (a.z + b.z);
+  const int2 ei = edges[I];
+  double acc[kPhi];
+  for (int k = 0; k < kPhi; ++k) acc[k] = 0.0;
+  for (int q = near_off[blockIdx.x]; q < near_off[blockIdx.x + 1]; ++q) {
+    const int4 sn = node[near_src[q]];
+    for (int c0 = 0; c0 < sn.y; c0 += 64) {
+      __syncthreads();
+      const int cnt = min(64, sn.y - c0);
+      if (tid < cnt) {
+        const int pj = sn.x + c0 + tid;
+        const int J = perm[pj];
+        const V4<double> qa = GA[J], qb = GB[J], qt = GT[J];
+        sx[tid][0] = 0.5 * (qa.x + qb.x);
+        sx[tid][1] = 0.5 * (qa.y + qb.y);
+        sx[tid][2] = 0.5 * (qa.z + qb.z);
+        st[tid][0] = qt.x;
+        st[tid][1] = qt.y;
+        st[tid][2] = qt.z;
+        se[tid] = edges[J];
+        for (int k = 0; k < kPsi; ++k) sp[tid][k] = psi[(size_t)kPsi * pj + k];
+      }
+      __syncthreads();
+      if (act)
+        for (int u = 0; u < cnt; ++u) {
+          const int2 ej = se[u];
+          if ((ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y)) continue;
+          double klo, khi;
+          bct_kernels(x0 - sx[u][0], x1 - sx[u][1], x2 - sx[u][2], t.x, t.y, t.z, st[u][0], st[u][1], st[u][2],
+                      half_expo, klo, khi);
+          for (int k = 0; k < 4; ++k) acc[k] += klo * sp[u][k];
+          acc[4] += khi * sp[u][0];
+          for (int k = 0; k < 9; ++k) acc[5 + k] += khi * sp[u][4 + k];
+        }
+    }
+  }
+  if (act)
+    for (int k = 0; k < kPhi; ++k) phi[(size_t)kPhi * p + k] += a.w * acc[k];
+}
+
+// Per edge: the kernel-matrix form's edge values (B0 part w (3), B part z^c (3 x 3)).
+// out[I] = (w (3), z (9)) with w = (K1) (E u) - K E u and z^c = (H1) s^c T - H (s^c T).
+__global__ void k_bct_edge_vals(const double* __restrict__ phi, const int* __restrict__ perm, const double* __restrict__ X,
+                                const int2* __restrict__ edges, const V4<double>* __restrict__ GA,
+                                const V4<double>* __restrict__ GT, int nE, double* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nE) return;
+  const int I = perm[p];
+  const int2 e = edges[I];
+  const double l = GA[I].w;
+  const V4<double> t = GT[I];
+  const double* f = phi + (size_t)kPhi * p;
+  double* o = out + 12 * (size_t)I;
+  const double tv[3] = {t.x, t.y, t.z};
+  for (int c = 0; c < 3; ++c) {
+    const double a = X[3 * e.x + c], b = X[3 * e.y + c];
+    o[c] = f[0] * 0.5 * (a + b) - f[1 + c];
+    const double s = (b - a) / l;
+    for (int k = 0; k < 3; ++k) o[3 + 3 * c + k] = f[4] * s * tv[k] - f[5 + 3 * c + k];
+  }
+}
+
+// Y_v = sum over incident edges of E^T w (1/2 w) and D^T z (+-T.z / l).
+__global__ void k_bct_gather(const double* __restrict__ ev, const int* __restrict__ inc_off,
+                             const int* __restrict__ inc, const V4<double>* __restrict__ GA,
+                             const V4<double>* __restrict__ GT, int nV, double* __restrict__ Y) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nV) return;
+  double y[3] = {0.0, 0.0, 0.0};
+  for (int q = inc_off[v]; q < inc_off[v + 1]; ++q) {
+    const int code = inc[q], I = code >> 1;
+    const double sg = (code & 1) ? 1.0 : -1.0;
+    const double* o = ev + 12 * (size_t)I;
+    const double l = GA[I].w;
+    const V4<double> t = GT[I];
+    for (int c = 0; c < 3; ++c) {
+      const double tz = t.x * o[3 + 3 * c] + t.y * o[4 + 3 * c] + t.z * o[5 + 3 * c];
+      y[c] += 0.5 * o[c] + sg * tz / l;
+    }
+  }
+  for (int c = 0; c < 3; ++c) Y[3 * v + c] = y[c];
+}
+
+// ---------------------------------------------------------------------------
+// host side: block lists from the BVH's node data
+// ---------------------------------------------------------------------------
+rc_status Bct::ensure(int nE_, int nodes_) {
+  if (nE == nE_ && cap_nodes >= nodes_ && psi) return RC_OK;
+  release();
+  auto al = [](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 16)) == hipSuccess; };
+  if (!al((void**)&psi, sizeof(double) * kPsi * (size_t)nE_) || !al((void**)&phi, sizeof(double) * kPhi * (size_t)nE_) ||
+      !al((void**)&ev, sizeof(double) * 12 * (size_t)nE_) || !al((void**)&Psi, sizeof(double) * kPsi * (size_t)nodes_) ||
+      !al((void**)&Phi, sizeof(double) * kPhi * (size_t)nodes_)) {
+    release();
+    set_error("allocation of the block cluster tree failed");
+    return RC_ERR_NOMEM;
+  }
+  nE = nE_;
+  cap_nodes = nodes_;
+  return RC_OK;
+}
+
+void Bct::release() {
+  void* ps[] = {psi, phi, ev, Psi, Phi, far_off, far_src, near_off, near_src, leaf_node};
+  for (void* p : ps)
+    if (p) hipFree(p);
+  psi = phi = ev = Psi = Phi = nullptr;
+  far_off = far_src = near_off = near_src = leaf_node = nullptr;
+  nE = cap_nodes = n_far = n_near = n_leaves = 0;
+  near_pairs = 0;
+  ready = false;
+}
+
+rc_status build_bct(const Curve& c, Bvh& bvh, Bct& bct, double theta, int leaf, hipStream_t s) {
+  RC_TRY(build_bvh(c, bvh, leaf, s));
+  const int nn = bvh.n_nodes;
+  std::vector<int4> node(nn);
+  std::vector<float4> na(nn);
+  std::vector<float2> nr(nn);
+  RC_HIP(hipMemcpyAsync(node.data(), bvh.node, sizeof(int4) * nn, hipMemcpyDeviceToHost, s));
+  RC_HIP(hipMemcpyAsync(na.data(), bvh.na, sizeof(float4) * nn, hipMemcpyDeviceToHost, s));
+  RC_HIP(hipMemcpyAsync(nr.data(), bvh.nr, sizeof(float2) * nn, hipMemcpyDeviceToHost, s));
+  RC_HIP(hipStreamSynchronize(s));
+  // split (root, root) breadth first; blocks go to the target node's lists
+  std::vector<std::vector<int>> far(nn), nearl(nn);
+  std::vector<int2> cur{make_int2(0, 0)}, next;
+  long long pairs = 0;
+  const float th = (float)theta;
+  while (!cur.empty()) {
+    next.clear();
+    for (const int2 blk : cur) {
+      const int T = blk.x, S = blk.y;
+      const float4 ct = na[T], cs = na[S];
+      const float dx = ct.x - cs.x, dy = ct.y - cs.y, dz = ct.z - cs.z;
+      const float dist = std::sqrt(dx * dx + dy * dy + dz * dz);
+      const bool adm = T != S && std::max(nr[T].x, nr[S].x) < th * dist && std::max(nr[T].y, nr[S].y) < th;
+      if (adm) {
+        far[T].push_back(S);
+        continue;
+      }
+      const bool lt = node[T].z < 0, ls = node[S].z < 0;
+      if (lt && ls) {
+        nearl[T].push_back(S);
+        pairs += (long long)node[T].y * node[S].y;
+        continue;
+      }
+      // split the internal side(s): both when both are internal
+      const int t0 = lt ? T : node[T].z, t1 = lt ? T : node[T].z + 1;
+      const int s0 = ls ? S : node[S].z, s1 = ls ? S : node[S].z + 1;
+      next.push_back(make_int2(t0, s0));
+      if (s1 != s0) next.push_back(make_int2(t0, s1));
+      if (t1 != t0) {
+        next.push_back(make_int2(t1, s0));
+        if (s1 != s0) next.push_back(make_int2(t1, s1));
+      }
+    }
+    cur.swap(next);
+  }
+  std::vector<int> foff(nn + 1, 0), fsrc, noff(1, 0), nsrc, lnode;
+  for (int T = 0; T < nn; ++T) {
+    foff[T + 1] = foff[T] + (int)far[T].size();
+    fsrc.insert(fsrc.end(), far[T].begin(), far[T].end());
+    if (node[T].z < 0) {
+      lnode.push_back(T);
+      nsrc.insert(nsrc.end(), nearl[T].begin(), nearl[T].end());
+      noff.push_back((int)nsrc.size());
+    }
+  }
+  RC_TRY(bct.ensure(c.nE, nn));
+  void* ps[] = {bct.far_off, bct.far_src, bct.near_off, bct.near_src, bct.leaf_node};
+  for (void* p : ps)
+    if (p) hipFree(p);
+  bct.far_off = bct.far_src = bct.near_off = bct.near_src = bct.leaf_node = nullptr;
+  auto up = [&](int** dst, const std::vector<int>& v) -> rc_status {
+    if (hipMalloc((void**)dst, sizeof(int) * std::max<size_t>(v.size(), 1)) != hipSuccess) {
+      set_error("allocation of the block lists failed");
+      return RC_ERR_NOMEM;
+    }
+    if (!v.empty()) RC_HIP(hipMemcpy(*dst, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice));
+    return RC_OK;
+  };
+  RC_TRY(up(&bct.far_off, foff));
+  RC_TRY(up(&bct.far_src, fsrc));
+  RC_TRY(up(&bct.near_off, noff));
+  RC_TRY(up(&bct.near_src, nsrc));
+  RC_TRY(up(&bct.leaf_node, lnode));
+  bct.n_nodes = nn;
+  bct.n_far = (int)fsrc.size();
+  bct.n_near = (int)nsrc.size();
+  bct.n_leaves = (int)lnode.size();
+  bct.near_pairs = pairs;
+  bct.theta = theta;
+  bct.ready = true;
+  return RC_OK;
+}
+
+rc_status launch_bct_apply(const Curve& c, const Bvh& bvh, Bct& bct, double alpha, double beta, const double* X,
+                           double* Y, hipStream_t s) {
+  if (!bct.ready) {
+    set_error("block cluster tree not built");
+    return RC_ERR_ARG;
+  }
+  const int nE = c.nE;
+  const double sigma = (beta - 1.0) / alpha - 1.0;
+  const double half_expo = 0.5 * (2.0 * sigma + 1.0);
+  const V4<double>*GA = c.gd.a, *GB = c.gd.b, *GT = c.gd.t;
+  hipLaunchKernelGGL(k_bct_rhs, dim3(bct_cdiv(nE, 256)), dim3(256), 0, s, X, (const int2*)c.edges, GA, GT,
+                     (const int*)bvh.perm, nE, bct.psi);
+  hipLaunchKernelGGL(k_bct_node_sums, dim3(bct.n_nodes), dim3(256), 0, s, (const int4*)bvh.node,
+                     (const double*)bct.psi, bct.Psi);
+  hipLaunchKernelGGL(k_bct_far, dim3(bct_cdiv(bct.n_nodes, 64)), dim3(64), 0, s, (const int*)bct.far_off,
+                     (const int*)bct.far_src, (const float4*)bvh.na, (const float4*)bvh.nb, (const double*)bct.Psi,
+                     bct.n_nodes, half_expo, bct.Phi);
+  hipLaunchKernelGGL(k_bct_down, dim3(bct_cdiv(nE, 256)), dim3(256), 0, s, (const int4*)bvh.node,
+                     (const double*)bct.Phi, GA, (const int*)bvh.perm, nE, bct.phi);
+  hipLaunchKernelGGL(k_bct_near, dim3(bct.n_leaves), dim3(64), 0, s, (const int*)bct.near_off,
+                     (const int*)bct.near_src, (const int*)bct.leaf_node, (const int4*)bvh.node,
+                     (const int*)bvh.perm, (const int2*)c.edges, GA, GB, GT, (const double*)bct.psi, half_expo,
+                     bct.phi);
+  hipLaunchKernelGGL(k_bct_edge_vals, dim3(bct_cdiv(nE, 256)), dim3(256), 0, s, (const double*)bct.phi,
+                     (const int*)bvh.perm, X, (const int2*)c.edges, GA, GT, nE, bct.ev);
+  hipLaunchKernelGGL(k_bct_gather, dim3(bct_cdiv(c.nV, 256)), dim3(256), 0, s, (const double*)bct.ev,
+                     (const int*)c.inc_off, (const int*)c.inc, GA, GT, c.nV, Y);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+}  // namespace rc

@@ -506,13 +506,8 @@ void Bvh::release() {
   nE = 0;
 }
 
-rc_status launch_bh(const Curve& c, Bvh& bvh, double alpha, double beta, double theta, int leaf, double* energy,
-                    double* dE, hipStream_t s) {
+rc_status build_bvh(const Curve& c, Bvh& bvh, int leaf, hipStream_t s) {
   const int nE = c.nE;
-  if (c.max_degree > 4) {
-    set_error("Barnes-Hut needs vertex degree <= 4 (a target keeps at most 6 neighbouring edges)");
-    return RC_ERR_UNSUPPORTED;
-  }
   RC_TRY(bvh.ensure(nE));
   hipLaunchKernelGGL(k_tangent_points, dim3(cdiv(nE, 256)), dim3(256), 0, s, c.gf.a, c.gf.b, c.gf.t, nE, bvh.pts,
                      bvh.perm);
@@ -539,8 +534,20 @@ rc_status launch_bh(const Curve& c, Bvh& bvh, double alpha, double beta, double 
   bvh.depth = levels;
   hipLaunchKernelGGL(k_bvh_props, dim3(bvh.n_nodes), dim3(kBvhThreads), 0, s, bvh.pts, c.gf.a, nE, bvh.node,
                      bvh.perm, bvh.na, bvh.nb, bvh.nr);
-  RC_HIP(hipMemsetAsync(bvh.work, 0, sizeof(unsigned long long) * 2, s));
   hipLaunchKernelGGL(k_invperm, dim3(cdiv(nE, 256)), dim3(256), 0, s, bvh.perm, nE, bvh.scratch);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+rc_status launch_bh(const Curve& c, Bvh& bvh, double alpha, double beta, double theta, int leaf, double* energy,
+                    double* dE, hipStream_t s) {
+  const int nE = c.nE;
+  if (c.max_degree > 4) {
+    set_error("Barnes-Hut needs vertex degree <= 4 (a target keeps at most 6 neighbouring edges)");
+    return RC_ERR_UNSUPPORTED;
+  }
+  RC_TRY(build_bvh(c, bvh, leaf, s));
+  RC_HIP(hipMemsetAsync(bvh.work, 0, sizeof(unsigned long long) * 2, s));
   const float ha = (float)(0.5 * alpha), hb = (float)(0.5 * beta), bb = (float)beta, th = (float)theta;
   dim3 g(cdiv(nE, 256)), b(256);
   const bool timed = c.timer && c.timer->on;

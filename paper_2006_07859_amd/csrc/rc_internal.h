@@ -249,6 +249,30 @@ struct Bvh {
   rc_status ensure(int nE_);
   void release();
 };
+// Block cluster tree over a BVH (k_bct.hip): per-edge and per-node sums of the
+// hierarchical product and the block lists (far blocks per target node,
+// near source leaves per target leaf).
+struct Bct {
+  int nE = 0, cap_nodes = 0, n_nodes = 0, n_far = 0, n_near = 0, n_leaves = 0;
+  long long near_pairs = 0;
+  double theta = 0.0;
+  bool ready = false;
+  double *psi = nullptr, *phi = nullptr, *ev = nullptr, *Psi = nullptr, *Phi = nullptr;
+  int *far_off = nullptr, *far_src = nullptr, *near_off = nullptr, *near_src = nullptr, *leaf_node = nullptr;
+  rc_status ensure(int nE_, int nodes_);
+  void release();
+};
+// Builds the BVH (nodes of at most leaf <= 64 edges) and the block cluster
+// tree of admissibility parameter theta at the curve's loaded geometry.
+rc_status build_bct(const Curve& c, Bvh& bvh, Bct& bct, double theta, int leaf, hipStream_t s);
+// Y = A^ X, the 0th-order hierarchical product with the kernel-matrix form of
+// A = B + B0 (needs the FP64 geometry of the build loaded).
+rc_status launch_bct_apply(const Curve& c, const Bvh& bvh, Bct& bct, double alpha, double beta, const double* X,
+                           double* Y, hipStream_t s);
+
+// Builds the BVH of the curve's current FP32 geometry (nodes of at most leaf
+// edges; node data and the inverse permutation in bvh.scratch).
+rc_status build_bvh(const Curve& c, Bvh& bvh, int leaf, hipStream_t s);
 // Barnes-Hut energy and differential in FP32 (needs the FP32 geometry).
 rc_status launch_bh(const Curve& c, Bvh& bvh, double alpha, double beta, double theta, int leaf, double* energy,
                     double* dE, hipStream_t s);

@@ -148,6 +148,8 @@ struct rc_ctx {
   rc::Dense dense;
   rc::Bvh bvh;
   rc::CcdBuffers ccd;
+  rc::Bvh bct_bvh;  // the block cluster tree's own BVH
+  rc::Bct bct;
   rc::KernelTimer timer;
   unsigned* status_dev = nullptr;  // device status word (RC_FLAG_* bits latched by kernels)
   unsigned status_host = 0;        // RC_FLAG_* bits latched by the host-side solver
