@@ -326,12 +326,12 @@ rc_status rc_step(rc_ctx* ctx, double* gamma, const rc_solve_opts* so, const rc_
 rc_status rc_first_collision_time(rc_ctx* ctx, const double* gamma, const double* D, double horizon, double* t);
 
 /* Block cluster tree (App. B.2): builds a BVH over the tangent-points of gamma
- * (leaves of at most leaf_size <= 64 edges, the builder of rc_bh_differential)
+ * (leaves of at most leaf_size <= 32 edges, the builder of rc_bh_differential)
  * and splits the block (root, root) recursively into blocks (T, S) of BVH
  * nodes; a block is a leaf when it is admissible (eq. BCTAdmissibilityTest:
  * max(r_x^T, r_x^S) < theta |c_T - c_S| and max(r_T^T, r_T^S) < theta) or
  * when both nodes are BVH leaves, otherwise its internal node(s) are split.
- * theta > 0, 1 <= leaf_size <= 64, else RC_ERR_ARG.  Synchronises (the block
+ * theta > 0, 1 <= leaf_size <= 32, else RC_ERR_ARG.  Synchronises (the block
  * lists are formed on the host from the node data).  The tree is kept until
  * the next build. */
 rc_status rc_bct_build(rc_ctx* ctx, const double* gamma, double theta, int32_t leaf_size);

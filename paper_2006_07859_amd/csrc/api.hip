@@ -415,8 +415,8 @@ rc_status rc_bct_build(rc_ctx* c, const double* gamma, double theta, int32_t lea
   RC_TRY(check_ctx(c));
   RC_TRY(no_batch(c, "rc_bct_build"));
   RC_TRY(check_ptrs({gamma}));
-  if (!(theta > 0.0) || !std::isfinite(theta) || leaf_size < 1 || leaf_size > 64) {
-    set_error("rc_bct_build: need theta > 0 and 1 <= leaf_size <= 64");
+  if (!(theta > 0.0) || !std::isfinite(theta) || leaf_size < 1 || leaf_size > 32) {
+    set_error("rc_bct_build: need theta > 0 and 1 <= leaf_size <= 32");
     return RC_ERR_ARG;
   }
   RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "pair_math.h"
 #include "rc_internal.h"
 
 namespace rc {
@@ -79,40 +80,54 @@ __global__ __launch_bounds__(256) void k_bct_node_sums(const int4* __restrict__ 
 }
 
 // The two kernels between tangent-points (x, T) and (y, U), d = x - y:
-// klo = (|T x d|^2 + |U x d|^2) |d|^-(2 sigma + 5), khi = 2 |d|^-(2 sigma + 1).
+// klo = (|T x d|^2 + |U x d|^2) |d|^-(2 sigma + 5), khi = 2 |d|^-(2 sigma + 1);
+// the powers of |d|^2 as in the operator's FP64 pair kernel (sob_powers).
+template <int EC>
 __device__ __forceinline__ void bct_kernels(double dx, double dy, double dz, double tx, double ty, double tz,
                                             double ux, double uy, double uz, double half_expo, double& klo,
                                             double& khi) {
   const double r2 = dx * dx + dy * dy + dz * dz;
   const double cx = ty * dz - tz * dy, cy = tz * dx - tx * dz, cz = tx * dy - ty * dx;
   const double ex = uy * dz - uz * dy, ey = uz * dx - ux * dz, ez = ux * dy - uy * dx;
-  const double p = pow(r2, -half_expo);  // |d|^-(2 sigma + 1)
+  double ri, p;
+  sob_powers<EC, double>(r2, half_expo, ri, p);  // ri = |d|^-2, p = |d|^-(2 sigma + 1)
   khi = 2.0 * p;
-  klo = (cx * cx + cy * cy + cz * cz + ex * ex + ey * ey + ez * ez) * p / (r2 * r2);
+  klo = (cx * cx + cy * cy + cz * cz + ex * ex + ey * ey + ez * ez) * p * ri * ri;
 }
 
 // Phi_T = sum over the admissible blocks (T, S) of klo(T, S) (Psi_S[0..3]) and
-// khi(T, S) (Psi_S[0], Psi_S[4..12]); one thread per node, blocks in list order.
-__global__ void k_bct_far(const int* __restrict__ far_off, const int* __restrict__ far_src,
-                          const float4* __restrict__ na, const float4* __restrict__ nb, const double* __restrict__ Psi,
-                          int n_nodes, double half_expo, double* __restrict__ Phi) {
-  const int T = blockIdx.x * blockDim.x + threadIdx.x;
-  if (T >= n_nodes) return;
+// khi(T, S) (Psi_S[0], Psi_S[4..12]); one wave per node, its lanes striding
+// over the node's blocks, then a fixed-order wave reduction.
+template <int EC>
+__global__ __launch_bounds__(256) void k_bct_far(const int* __restrict__ far_off, const int* __restrict__ far_src,
+                                                 const float4* __restrict__ na, const float4* __restrict__ nb,
+                                                 const double* __restrict__ Psi, int n_nodes, double half_expo,
+                                                 double* __restrict__ Phi) {
+  const int T = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (T >= n_nodes) return;  // uniform per wave
   double a[kPhi];
   for (int k = 0; k < kPhi; ++k) a[k] = 0.0;
   const float4 ct = na[T], tt = nb[T];
-  for (int q = far_off[T]; q < far_off[T + 1]; ++q) {
+  for (int q = far_off[T] + lane; q < far_off[T + 1]; q += 64) {
     const int S = far_src[q];
     const float4 cs = na[S], ts = nb[S];
     double klo, khi;
-    bct_kernels((double)ct.x - cs.x, (double)ct.y - cs.y, (double)ct.z - cs.z, tt.x, tt.y, tt.z, ts.x, ts.y, ts.z,
-                half_expo, klo, khi);
+    bct_kernels<EC>((double)ct.x - cs.x, (double)ct.y - cs.y, (double)ct.z - cs.z, tt.x, tt.y, tt.z, ts.x, ts.y,
+                    ts.z, half_expo, klo, khi);
     const double* P = Psi + (size_t)kPsi * S;
     for (int k = 0; k < 4; ++k) a[k] += klo * P[k];
     a[4] += khi * P[0];
     for (int k = 0; k < 9; ++k) a[5 + k] += khi * P[4 + k];
   }
-  for (int k = 0; k < kPhi; ++k) Phi[(size_t)kPhi * T + k] = a[k];
+#pragma unroll
+  for (int k = 0; k < kPhi; ++k)
+    for (int o = 32; o > 0; o >>= 1) a[k] += __shfl_xor(a[k], o);
+  if (lane < kPhi) {
+    double v = a[0];
+#pragma unroll
+    for (int k = 1; k < kPhi; ++k) v = lane == k ? a[k] : v;
+    Phi[(size_t)kPhi * T + lane] = v;
+  }
 }
 
 // phi[p] = l_J (sum of Phi over the ancestors of position p, root included).
@@ -135,19 +150,25 @@ __global__ void k_bct_down(const int4* __restrict__ node, const double* __restri
   for (int k = 0; k < kPhi; ++k) phi[(size_t)kPhi * p + k] = l * a[k];
 }
 
-// Exact near blocks: one workgroup of 64 per target leaf T, a thread per edge
-// of T; every near source leaf S of T in list order, its edges staged in LDS.
-__global__ __launch_bounds__(64) void k_bct_near(const int* __restrict__ near_off, const int* __restrict__ near_src,
-                                                 const int* __restrict__ leaf_node, const int4* __restrict__ node,
-                                                 const int* __restrict__ perm, const int2* __restrict__ edges,
-                                                 const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB,
-                                                 const V4<double>* __restrict__ GT, const double* __restrict__ psi,
-                                                 double half_expo, double* __restrict__ phi) {
-  __shared__ double sx[64][3], st[64][3], sp[64][kPsi];
-  __shared__ int2 se[64];
+// Exact near blocks: one workgroup of 256 per target leaf T (at most 32 edges):
+// eight groups of 32 threads take the leaf's near source leaves in turn
+// (group j the blocks j, j + 8, ...), a thread per target edge, each group
+// staging its source leaf in its own LDS slice; the eight partial sums are
+// added in group order.
+constexpr int kNearGroups = 8;
+template <int EC>
+__global__ __launch_bounds__(256) void k_bct_near(const int* __restrict__ near_off, const int* __restrict__ near_src,
+                                                  const int* __restrict__ leaf_node, const int4* __restrict__ node,
+                                                  const int* __restrict__ perm, const int2* __restrict__ edges,
+                                                  const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB,
+                                                  const V4<double>* __restrict__ GT, const double* __restrict__ psi,
+                                                  double half_expo, double* __restrict__ phi) {
+  __shared__ double sx[kNearGroups][32][3], st[kNearGroups][32][3], sp[kNearGroups][32][kPsi];
+  __shared__ int2 se[kNearGroups][32];
+  __shared__ double red[kNearGroups][32][kPhi];
   const int Tn = leaf_node[blockIdx.x];
   const int4 tn = node[Tn];
-  const int tid = threadIdx.x;
+  const int grp = threadIdx.x / 32, tid = threadIdx.x % 32;
   const bool act = tid < tn.y;
   const int p = tn.x + (act ? tid : 0);
   const int I = perm[p];
@@ -156,40 +177,49 @@ __global__ __launch_bounds__(64) void k_bct_near(const int* __restrict__ near_of
   const int2 ei = edges[I];
   double acc[kPhi];
   for (int k = 0; k < kPhi; ++k) acc[k] = 0.0;
-  for (int q = near_off[blockIdx.x]; q < near_off[blockIdx.x + 1]; ++q) {
-    const int4 sn = node[near_src[q]];
-    for (int c0 = 0; c0 < sn.y; c0 += 64) {
-      __syncthreads();
-      const int cnt = min(64, sn.y - c0);
-      if (tid < cnt) {
-        const int pj = sn.x + c0 + tid;
-        const int J = perm[pj];
-        const V4<double> qa = GA[J], qb = GB[J], qt = GT[J];
-        sx[tid][0] = 0.5 * (qa.x + qb.x);
-        sx[tid][1] = 0.5 * (qa.y + qb.y);
-        sx[tid][2] = 0.5 * (qa.z + qb.z);
-        st[tid][0] = qt.x;
-        st[tid][1] = qt.y;
-        st[tid][2] = qt.z;
-        se[tid] = edges[J];
-        for (int k = 0; k < kPsi; ++k) sp[tid][k] = psi[(size_t)kPsi * pj + k];
+  const int q0 = near_off[blockIdx.x], q1 = near_off[blockIdx.x + 1];
+  // every group runs the same number of rounds, so the barriers match
+  const int rounds = (q1 - q0 + kNearGroups - 1) / kNearGroups;
+  for (int r = 0; r < rounds; ++r) {
+    const int q = q0 + r * kNearGroups + grp;
+    const bool has = q < q1;
+    const int4 sn = has ? node[near_src[q]] : make_int4(0, 0, -1, 0);
+    __syncthreads();
+    if (tid < sn.y) {
+      const int pj = sn.x + tid;
+      const int J = perm[pj];
+      const V4<double> qa = GA[J], qb = GB[J], qt = GT[J];
+      sx[grp][tid][0] = 0.5 * (qa.x + qb.x);
+      sx[grp][tid][1] = 0.5 * (qa.y + qb.y);
+      sx[grp][tid][2] = 0.5 * (qa.z + qb.z);
+      st[grp][tid][0] = qt.x;
+      st[grp][tid][1] = qt.y;
+      st[grp][tid][2] = qt.z;
+      se[grp][tid] = edges[J];
+      for (int k = 0; k < kPsi; ++k) sp[grp][tid][k] = psi[(size_t)kPsi * pj + k];
+    }
+    __syncthreads();
+    if (act)
+      for (int u = 0; u < sn.y; ++u) {
+        const int2 ej = se[grp][u];
+        if ((ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y)) continue;
+        double klo, khi;
+        bct_kernels<EC>(x0 - sx[grp][u][0], x1 - sx[grp][u][1], x2 - sx[grp][u][2], t.x, t.y, t.z, st[grp][u][0],
+                        st[grp][u][1], st[grp][u][2], half_expo, klo, khi);
+        for (int k = 0; k < 4; ++k) acc[k] += klo * sp[grp][u][k];
+        acc[4] += khi * sp[grp][u][0];
+        for (int k = 0; k < 9; ++k) acc[5 + k] += khi * sp[grp][u][4 + k];
       }
-      __syncthreads();
-      if (act)
-        for (int u = 0; u < cnt; ++u) {
-          const int2 ej = se[u];
-          if ((ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y)) continue;
-          double klo, khi;
-          bct_kernels(x0 - sx[u][0], x1 - sx[u][1], x2 - sx[u][2], t.x, t.y, t.z, st[u][0], st[u][1], st[u][2],
-                      half_expo, klo, khi);
-          for (int k = 0; k < 4; ++k) acc[k] += klo * sp[u][k];
-          acc[4] += khi * sp[u][0];
-          for (int k = 0; k < 9; ++k) acc[5 + k] += khi * sp[u][4 + k];
-        }
+  }
+  for (int k = 0; k < kPhi; ++k) red[grp][tid][k] = acc[k];
+  __syncthreads();
+  if (grp == 0 && act) {
+    for (int k = 0; k < kPhi; ++k) {
+      double v = red[0][tid][k];
+      for (int g = 1; g < kNearGroups; ++g) v += red[g][tid][k];
+      phi[(size_t)kPhi * p + k] += a.w * v;
     }
   }
-  if (act)
-    for (int k = 0; k < kPhi; ++k) phi[(size_t)kPhi * p + k] += a.w * acc[k];
 }
 
 // Per edge: the kernel-matrix form's edge values (B0 part w (3), B part z^c (3 x 3)).
@@ -362,15 +392,23 @@ rc_status launch_bct_apply(const Curve& c, const Bvh& bvh, Bct& bct, double alph
                      (const int*)bvh.perm, nE, bct.psi);
   hipLaunchKernelGGL(k_bct_node_sums, dim3(bct.n_nodes), dim3(256), 0, s, (const int4*)bvh.node,
                      (const double*)bct.psi, bct.Psi);
-  hipLaunchKernelGGL(k_bct_far, dim3(bct_cdiv(bct.n_nodes, 64)), dim3(64), 0, s, (const int*)bct.far_off,
-                     (const int*)bct.far_src, (const float4*)bvh.na, (const float4*)bvh.nb, (const double*)bct.Psi,
-                     bct.n_nodes, half_expo, bct.Phi);
-  hipLaunchKernelGGL(k_bct_down, dim3(bct_cdiv(nE, 256)), dim3(256), 0, s, (const int4*)bvh.node,
-                     (const double*)bct.Phi, GA, (const int*)bvh.perm, nE, bct.phi);
-  hipLaunchKernelGGL(k_bct_near, dim3(bct.n_leaves), dim3(64), 0, s, (const int*)bct.near_off,
-                     (const int*)bct.near_src, (const int*)bct.leaf_node, (const int4*)bvh.node,
-                     (const int*)bvh.perm, (const int2*)c.edges, GA, GB, GT, (const double*)bct.psi, half_expo,
-                     bct.phi);
+  auto far_near = [&](auto ec) {
+    constexpr int EC = decltype(ec)::value;
+    hipLaunchKernelGGL((k_bct_far<EC>), dim3(bct_cdiv(bct.n_nodes, 4)), dim3(256), 0, s, (const int*)bct.far_off,
+                       (const int*)bct.far_src, (const float4*)bvh.na, (const float4*)bvh.nb,
+                       (const double*)bct.Psi, bct.n_nodes, half_expo, bct.Phi);
+    hipLaunchKernelGGL(k_bct_down, dim3(bct_cdiv(nE, 256)), dim3(256), 0, s, (const int4*)bvh.node,
+                       (const double*)bct.Phi, GA, (const int*)bvh.perm, nE, bct.phi);
+    hipLaunchKernelGGL((k_bct_near<EC>), dim3(bct.n_leaves), dim3(256), 0, s, (const int*)bct.near_off,
+                       (const int*)bct.near_src, (const int*)bct.leaf_node, (const int4*)bvh.node,
+                       (const int*)bvh.perm, (const int2*)c.edges, GA, GB, GT, (const double*)bct.psi, half_expo,
+                       bct.phi);
+  };
+  switch (exp_case(alpha, beta)) {
+    case kA2B4: far_near(std::integral_constant<int, kA2B4>{}); break;
+    case kA2B45: far_near(std::integral_constant<int, kA2B45>{}); break;
+    default: far_near(std::integral_constant<int, kGeneral>{}); break;
+  }
   hipLaunchKernelGGL(k_bct_edge_vals, dim3(bct_cdiv(nE, 256)), dim3(256), 0, s, (const double*)bct.phi,
                      (const int*)bvh.perm, X, (const int2*)c.edges, GA, GT, nE, bct.ev);
   hipLaunchKernelGGL(k_bct_gather, dim3(bct_cdiv(c.nV, 256)), dim3(256), 0, s, (const double*)bct.ev,

@@ -262,7 +262,7 @@ struct Bct {
   rc_status ensure(int nE_, int nodes_);
   void release();
 };
-// Builds the BVH (nodes of at most leaf <= 64 edges) and the block cluster
+// Builds the BVH (nodes of at most leaf <= 32 edges) and the block cluster
 // tree of admissibility parameter theta at the curve's loaded geometry.
 rc_status build_bct(const Curve& c, Bvh& bvh, Bct& bct, double theta, int leaf, hipStream_t s);
 // Y = A^ X, the 0th-order hierarchical product with the kernel-matrix form of

@@ -105,7 +105,7 @@ def test_bct_error_curve_32k(lib):
     t = 2 * np.pi * np.arange(n) / n
     X = np.stack([np.cos(t), np.sin(2 * t), np.cos(3 * t)], 1) + 1e-3 * np.random.default_rng(3).normal(size=(n, 3))
     ctx = Context(n, e, 2.0, 4.5, RC_F32)
-    ref, _ = bct_apply(ctx, g, X, 1e-6, leaf=64)
+    ref, _ = bct_apply(ctx, g, X, 1e-6)
     prev, errs = None, {}
     for theta in (0.1, 0.25, 0.5):
         gam = dev(g)
