@@ -120,6 +120,12 @@ typedef struct {
   int32_t fallback_after; /* multilevel and learned preconditioners: when > 0, stop after the residual
                              has grown in this many consecutive iterations, or at max_iter, and solve
                              again with the multigrid preconditioner (rc_stats.fallback = 1) */
+  double bct_theta;      /* > 0: the operator of the finest level and of every multigrid level with at
+                            least bct_min_vertices vertices is the block-cluster-tree product of
+                            rc_sobolev_apply_bct (App. B.2) with this admissibility parameter, each level
+                            with its own tree built at its curve (the PCG residual and the line search's
+                            projection solves use it too); needs lowp = 0.  0 = exact operators */
+  int32_t bct_min_vertices;
 } rc_solve_opts;
 
 /* Options of the batch step (rc_batch_step). */

@@ -56,7 +56,7 @@ class SolveOpts(C.Structure):
                 ("replace_every", C.c_int32), ("mg_min_vertices", C.c_int32), ("cheb_degree", C.c_int32),
                 ("op_f64", C.c_int32), ("lowp", C.c_int32), ("lowp_band", C.c_int32),
                 ("lowp_min_vertices", C.c_int32), ("lowp_outer", C.c_int32), ("inner_tol", C.c_double),
-                ("fallback_after", C.c_int32)]
+                ("fallback_after", C.c_int32), ("bct_theta", C.c_double), ("bct_min_vertices", C.c_int32)]
 
 
 class BatchOpts(C.Structure):

@@ -103,6 +103,8 @@ void rc_default_solve_opts(rc_solve_opts* o) {
   o->lowp_outer = 0;
   o->inner_tol = 0.0;
   o->fallback_after = 10;
+  o->bct_theta = 0.0;
+  o->bct_min_vertices = 32768;
 }
 
 void rc_default_ls_opts(rc_ls_opts* o) {

@@ -37,6 +37,7 @@ static inline int bct_cdiv(int a, int b) { return (a + b - 1) / b; }
 
 constexpr int kPsi = 13;   // 1, E u (3), s^c T (9); times l_J
 constexpr int kPhi = 14;   // K: 1, E u (3); H: 1, s^c T (9)
+constexpr int kEv = 14;    // per-edge values: w (3), z (9), K1, H1
 
 // Per edge J at BVH position p: psi[p][0..12].
 __global__ void k_bct_rhs(const double* __restrict__ X, const int2* __restrict__ edges,
@@ -222,8 +223,9 @@ __global__ __launch_bounds__(256) void k_bct_near(const int* __restrict__ near_o
   }
 }
 
-// Per edge: the kernel-matrix form's edge values (B0 part w (3), B part z^c (3 x 3)).
-// out[I] = (w (3), z (9)) with w = (K1) (E u) - K E u and z^c = (H1) s^c T - H (s^c T).
+// Per edge: the kernel-matrix form's edge values (B0 part w (3), B part z^c (3 x 3))
+// and the row sums: out[I] = (w (3), z (9), (K1)_I, (H1)_I) with
+// w = (K1) (E u) - K E u and z^c = (H1) s^c T - H (s^c T).
 __global__ void k_bct_edge_vals(const double* __restrict__ phi, const int* __restrict__ perm, const double* __restrict__ X,
                                 const int2* __restrict__ edges, const V4<double>* __restrict__ GA,
                                 const V4<double>* __restrict__ GT, int nE, double* __restrict__ out) {
@@ -234,7 +236,9 @@ __global__ void k_bct_edge_vals(const double* __restrict__ phi, const int* __res
   const double l = GA[I].w;
   const V4<double> t = GT[I];
   const double* f = phi + (size_t)kPhi * p;
-  double* o = out + 12 * (size_t)I;
+  double* o = out + kEv * (size_t)I;
+  o[12] = f[0];
+  o[13] = f[4];
   const double tv[3] = {t.x, t.y, t.z};
   for (int c = 0; c < 3; ++c) {
     const double a = X[3 * e.x + c], b = X[3 * e.y + c];
@@ -244,25 +248,31 @@ __global__ void k_bct_edge_vals(const double* __restrict__ phi, const int* __res
   }
 }
 
-// Y_v = sum over incident edges of E^T w (1/2 w) and D^T z (+-T.z / l).
+// Y_v = sum over incident edges of E^T w (1/2 w) and D^T z (+-T.z / l); with
+// diag, the diagonal of the same operator: the diagonal of E^T (diag(K1) - K) E
+// is 1/4 sum_{I at v} (K1)_I and that of D^T (diag(H1) - H) D is
+// sum_{I at v} (H1)_I / l_I^2 (K and H vanish on pairs sharing v).
 __global__ void k_bct_gather(const double* __restrict__ ev, const int* __restrict__ inc_off,
                              const int* __restrict__ inc, const V4<double>* __restrict__ GA,
-                             const V4<double>* __restrict__ GT, int nV, double* __restrict__ Y) {
+                             const V4<double>* __restrict__ GT, int nV, double* __restrict__ Y,
+                             double* __restrict__ diag) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nV) return;
-  double y[3] = {0.0, 0.0, 0.0};
+  double y[3] = {0.0, 0.0, 0.0}, dg = 0.0;
   for (int q = inc_off[v]; q < inc_off[v + 1]; ++q) {
     const int code = inc[q], I = code >> 1;
     const double sg = (code & 1) ? 1.0 : -1.0;
-    const double* o = ev + 12 * (size_t)I;
+    const double* o = ev + kEv * (size_t)I;
     const double l = GA[I].w;
     const V4<double> t = GT[I];
     for (int c = 0; c < 3; ++c) {
       const double tz = t.x * o[3 + 3 * c] + t.y * o[4 + 3 * c] + t.z * o[5 + 3 * c];
       y[c] += 0.5 * o[c] + sg * tz / l;
     }
+    dg += 0.25 * o[12] + o[13] / (l * l);
   }
   for (int c = 0; c < 3; ++c) Y[3 * v + c] = y[c];
+  if (diag) diag[v] = dg;
 }
 
 // ---------------------------------------------------------------------------
@@ -273,7 +283,7 @@ rc_status Bct::ensure(int nE_, int nodes_) {
   release();
   auto al = [](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 16)) == hipSuccess; };
   if (!al((void**)&psi, sizeof(double) * kPsi * (size_t)nE_) || !al((void**)&phi, sizeof(double) * kPhi * (size_t)nE_) ||
-      !al((void**)&ev, sizeof(double) * 12 * (size_t)nE_) || !al((void**)&Psi, sizeof(double) * kPsi * (size_t)nodes_) ||
+      !al((void**)&ev, sizeof(double) * kEv * (size_t)nE_) || !al((void**)&Psi, sizeof(double) * kPsi * (size_t)nodes_) ||
       !al((void**)&Phi, sizeof(double) * kPhi * (size_t)nodes_)) {
     release();
     set_error("allocation of the block cluster tree failed");
@@ -379,7 +389,7 @@ rc_status build_bct(const Curve& c, Bvh& bvh, Bct& bct, double theta, int leaf, 
 }
 
 rc_status launch_bct_apply(const Curve& c, const Bvh& bvh, Bct& bct, double alpha, double beta, const double* X,
-                           double* Y, hipStream_t s) {
+                           double* Y, hipStream_t s, double* diag) {
   if (!bct.ready) {
     set_error("block cluster tree not built");
     return RC_ERR_ARG;
@@ -412,7 +422,7 @@ rc_status launch_bct_apply(const Curve& c, const Bvh& bvh, Bct& bct, double alph
   hipLaunchKernelGGL(k_bct_edge_vals, dim3(bct_cdiv(nE, 256)), dim3(256), 0, s, (const double*)bct.phi,
                      (const int*)bvh.perm, X, (const int2*)c.edges, GA, GT, nE, bct.ev);
   hipLaunchKernelGGL(k_bct_gather, dim3(bct_cdiv(c.nV, 256)), dim3(256), 0, s, (const double*)bct.ev,
-                     (const int*)c.inc_off, (const int*)c.inc, GA, GT, c.nV, Y);
+                     (const int*)c.inc_off, (const int*)c.inc, GA, GT, c.nV, Y, diag);
   RC_HIP(hipGetLastError());
   return RC_OK;
 }

@@ -165,6 +165,8 @@ struct Curve {
 
   KernelTimer* timer = nullptr;    // set on the finest level when profiling is on
   unsigned* status = nullptr;      // the context's device status word (not owned); null on coarse levels
+  const struct Bvh* hbvh = nullptr; // when set (with hbct): the solver applies this level's operator as the
+  struct Bct* hbct = nullptr;       // block-cluster-tree product of that tree (not owned)
 
   int nchunk = 1, src_per_chunk = 0;
   int part_chunks = 0;             // chunks part has room for (the near band uses chunk nchunk)
@@ -267,8 +269,10 @@ struct Bct {
 rc_status build_bct(const Curve& c, Bvh& bvh, Bct& bct, double theta, int leaf, hipStream_t s);
 // Y = A^ X, the 0th-order hierarchical product with the kernel-matrix form of
 // A = B + B0 (needs the FP64 geometry of the build loaded).
+// diag (optional, [nV]): the diagonal of that approximate A, from the same row
+// sums (diag_v = 1/4 sum_{I at v} (K 1)_I + sum_{I at v} (H 1)_I / l_I^2).
 rc_status launch_bct_apply(const Curve& c, const Bvh& bvh, Bct& bct, double alpha, double beta, const double* X,
-                           double* Y, hipStream_t s);
+                           double* Y, hipStream_t s, double* diag = nullptr);
 
 // Builds the BVH of the curve's current FP32 geometry (nodes of at most leaf
 // edges; node data and the inverse permutation in bvh.scratch).

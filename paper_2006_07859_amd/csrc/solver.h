@@ -63,6 +63,8 @@ struct Level {
   int *restr_off = nullptr, *restr_idx = nullptr;  // coarse vertex -> fine vertices that reference it
   double* gamma = nullptr; // the level's vertex positions [nV][3]
   LowpOp lowp;             // assembled 16-bit operator of the level (precision path)
+  Bvh bvh;                 // the level's block cluster tree (hierarchical operator)
+  Bct bct;
 };
 
 struct MGLevelState {
@@ -150,6 +152,8 @@ struct rc_ctx {
   rc::CcdBuffers ccd;
   rc::Bvh bct_bvh;  // the block cluster tree's own BVH
   rc::Bct bct;
+  double bct_theta = 0.0;  // the solver's hierarchical operator (0 = exact)
+  int bct_min_v = 0;
   rc::KernelTimer timer;
   unsigned* status_dev = nullptr;  // device status word (RC_FLAG_* bits latched by kernels)
   unsigned status_host = 0;        // RC_FLAG_* bits latched by the host-side solver

@@ -630,6 +630,8 @@ void mg_free(rc_ctx* c) {
       dfree(L->restr_idx);
       dfree(L->gamma);
       L->lowp.release();
+      L->bvh.release();
+      L->bct.release();
     }
   c->levels.clear();
   cons_free(c->cons_w);
@@ -737,7 +739,10 @@ static rc_status mg_build(rc_ctx* c) {
   return RC_OK;
 }
 
+// A X on a level: the block-cluster-tree product when the level has a tree
+// (FP64 sums whatever prec), else the matrix-free operator in precision prec.
 static rc_status apply_A(rc_ctx* c, const Curve& cv, const double* X, double* Y, rc_dtype prec) {
+  if (cv.hbct) return launch_bct_apply(cv, *cv.hbvh, *cv.hbct, c->alpha, c->beta, X, Y, c->stream);
   return launch_sobolev(cv, c->alpha, c->beta, prec, X, Y, nullptr, c->stream);
 }
 
@@ -763,10 +768,21 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
     g = L.gamma;
   }
   for (int l = 0; l < nl; ++l) {
-    const Curve& cv = level_curve(c, l);
+    Curve& cv = const_cast<Curve&>(level_curve(c, l));
     const double* gl = l == 0 ? gamma : c->levels[l]->gamma;
     RC_TRY(launch_geometry(cv, gl, RC_F32, s));
     if (l > 0) RC_TRY(cons_prepare(c, cv, level_cons(c, l), gl));
+    // hierarchical operator: a block cluster tree of the level at its curve (not on the
+    // coarsest level, whose dense saddle is assembled exactly)
+    cv.hbvh = nullptr;
+    cv.hbct = nullptr;
+    if (c->bct_theta > 0.0 && l < nl - 1 && cv.nV >= c->bct_min_v) {
+      Bvh& bv = l == 0 ? c->bct_bvh : c->levels[l]->bvh;
+      Bct& bt = l == 0 ? c->bct : c->levels[l]->bct;
+      RC_TRY(build_bct(cv, bv, bt, c->bct_theta, 32, s));
+      cv.hbvh = &bv;
+      cv.hbct = &bt;
+    }
   }
   const rc_dtype prec = c->dtype;
   // the smoothers' weighted projector needs every smoothed level's border in the fused projector
@@ -780,6 +796,8 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
     if (l < c->lowp_levels)
       RC_TRY(launch_assemble_lowp(cv, level_lowp(c, l), c->lowp_fmt, c->lowp_band, l == 0 && c->lowp_outer == 1,
                                   c->alpha, c->beta, st.diag, s));
+    else if (cv.hbct)
+      RC_TRY(launch_bct_apply(cv, *cv.hbvh, *cv.hbct, c->alpha, c->beta, st.pw, st.t, s, st.diag));
     else
       RC_TRY(launch_sobolev(cv, c->alpha, c->beta, prec, st.pw, st.t, st.diag, s));
     if (c->mg_weighted) {  // factors of C W C^T, W = D^-1
@@ -1106,6 +1124,20 @@ rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o)
     return RC_ERR_ARG;
   }
   c->lowp_levels = 0;
+  if (o.bct_theta < 0.0 || (o.bct_theta > 0.0 && (o.lowp || o.solver != RC_SOLVE_PCG_MG))) {
+    set_error("solve options: the block-cluster-tree operator (bct_theta > 0) serves the multigrid solver "
+              "without the precision path");
+    return RC_ERR_ARG;
+  }
+  c->bct_theta = o.bct_theta;
+  c->bct_min_v = std::max(1, o.bct_min_vertices);
+  c->curve.hbvh = nullptr;
+  c->curve.hbct = nullptr;
+  for (auto& L : c->levels)
+    if (L) {
+      L->curve.hbvh = nullptr;
+      L->curve.hbct = nullptr;
+    }
   RC_TRY(load_geometry(c, gamma));
   RC_TRY(cons_prepare(c, c->curve, c->cons, gamma));
   if (o.solver == RC_SOLVE_DENSE) return dense_prepare(c, c->curve, c->cons, c->dense, gamma);

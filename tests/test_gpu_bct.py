@@ -128,3 +128,79 @@ def test_bct_error_curve_32k(lib):
         prev = errs[theta] = err
     assert errs[0.1] < 1e-4 and errs[0.25] < 5e-3
     ctx.close()
+
+
+def test_bct_projected_gradient_limit(lib):
+    """The multigrid PCG solve with every smoothed level's operator on its own
+    block cluster tree: as theta -> 0 its projected gradient is the oracle's
+    dense saddle solution for the kernel-matrix form of A (eq.
+    GradientSaddlePointProblem with A of App. B.3.4); at theta > 0 the gap
+    follows the operator's error."""
+    from paper_2006_07859_amd import (RC_C_BARYCENTER, RC_C_EDGE_LENGTH, RC_F32, RC_SOLVE_PCG_MG, Context,
+                                      default_solve_opts)
+    from oracle import constraints as cons
+    from oracle import solve, tpe
+
+    n, a, b = 2048, 2.0, 4.5
+    banner(f"projected gradient on the block cluster tree, fourier knot {n} edges")
+    g, e, _ = gen.fourier_knot(n, seed=0)
+    g = gen.round_to_f32(g)
+    mask = RC_C_BARYCENTER | RC_C_EDGE_LENGTH
+    refs = cons.reference_values(g, e)
+    _, dE = tpe.differential(g, e, a, b)
+    A = sum(sobolev.assemble(g, e, a, b, quadrature="midpoint"))
+    _, C = cons.evaluate(g, e, mask, *refs)
+    g_ref, _ = solve.projected_gradient_structured(A, C, dE)
+    ctx = Context(n, e, a, b, RC_F32)
+    gam = dev(g)
+    ctx.rc_set_constraints(mask, gam)
+    errs = {}
+    for theta in (1e-6, 0.1, 0.25):
+        so = default_solve_opts(solver=RC_SOLVE_PCG_MG, tol=1e-10, mg_min_vertices=256, cheb_degree=2, op_f64=1,
+                                max_iter=300, bct_theta=theta, bct_min_vertices=512)
+        out = zeros(n, 3)
+        st = ctx.rc_sobolev_gradient(gam, dev(dE), out, so)
+        errs[theta] = relnorm(host(out), g_ref)
+        print(f"  theta {theta}: {st['iterations']} iterations, res {st['residual']:.1e}, rel error {errs[theta]:.2e}")
+    assert errs[1e-6] < 1e-7
+    assert errs[0.1] < errs[0.25] < 2e-2
+    ctx.close()
+
+
+def test_bct_step_262k(lib):
+    """A full projected Sobolev step (differential, multigrid PCG on the block
+    cluster tree operator to 1e-6, projected line search with edge-length and
+    barycenter restoration) at 262,144 edges, theta 0.25: the energy falls and
+    the constraints hold at the new curve."""
+    import time
+
+    import torch
+
+    from paper_2006_07859_amd import (RC_C_BARYCENTER, RC_C_EDGE_LENGTH, RC_F32, RC_SOLVE_PCG_MG, Context,
+                                      default_ls_opts, default_solve_opts)
+
+    n = 262144
+    banner(f"projected Sobolev step on the block cluster tree, fourier knot {n} edges")
+    g, e, _ = gen.fourier_knot(n, seed=0)
+    g = gen.round_to_f32(g)
+    ctx = Context(n, e, 2.0, 4.5, RC_F32)
+    gam = dev(g)
+    ctx.rc_set_constraints(RC_C_BARYCENTER | RC_C_EDGE_LENGTH, gam)
+    so = default_solve_opts(solver=RC_SOLVE_PCG_MG, tol=1e-6, mg_min_vertices=256, cheb_degree=2, op_f64=1,
+                            max_iter=200, bct_theta=0.25, bct_min_vertices=16384)
+    for k in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.rc_step(gam, so=so, ls=default_ls_opts())
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        print(f"  step {k}: {ms:.0f} ms  E {st['energy']:.8g} -> {st['energy_new']:.8g}  pcg {st['iterations']} it  "
+              f"res {st['residual']:.1e}  tau {st['tau']:.3g}  eval {st['t_eval_ms']:.1f} ms  solve "
+              f"{st['t_solve_ms']:.1f} ms  search {st['t_search_ms']:.1f} ms")
+        assert st["energy_new"] < st["energy"]
+        assert st["residual"] <= 1e-6
+    phi = zeros(ctx.rc_constraint_count())
+    ctx.rc_constraint_values(gam, phi)
+    lbar = float(np.mean(np.linalg.norm(g[e[:, 1]] - g[e[:, 0]], axis=1)))
+    assert np.abs(host(phi)[3:]).max() < 1e-9 * lbar  # the line search projects to 1e-10 mean edge lengths
+    ctx.close()
