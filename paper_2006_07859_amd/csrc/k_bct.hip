@@ -20,7 +20,7 @@
 //
 // Product (all sums in FP64, in fixed orders): per-edge right-hand sides
 // psi_J = l_J (1, (E u)_J, s_J^c T_J) (13 values, s^c = (u^c_j2 - u^c_j1) / l_J),
-// per-node sums Psi_S (contiguous ranges of the BVH permutation), per target
+// per-node sums Psi_S (contiguous ranges of the BVH permutation, summed bottom-up), per target
 // node the admissible blocks' Phi_T = sum_S k(p_T, p_S) Psi_S, pushed down to
 // every edge through its ancestors, the exact near blocks per target leaf,
 // then the diagonal and off-diagonal parts combined and gathered to vertices.
@@ -61,23 +61,35 @@ __global__ void k_bct_rhs(const double* __restrict__ X, const int2* __restrict__
   }
 }
 
-// Psi_S = sum of psi over the node's range; one workgroup per node.
-__global__ __launch_bounds__(256) void k_bct_node_sums(const int4* __restrict__ node, const double* __restrict__ psi,
-                                                       double* __restrict__ Psi) {
-  __shared__ double sm[kPsi][256];
-  const int4 nd = node[blockIdx.x];
-  double a[kPsi];
-  for (int k = 0; k < kPsi; ++k) a[k] = 0.0;
-  for (int i = threadIdx.x; i < nd.y; i += 256)
-    for (int k = 0; k < kPsi; ++k) a[k] += psi[(size_t)kPsi * (nd.x + i) + k];
-  for (int k = 0; k < kPsi; ++k) sm[k][threadIdx.x] = a[k];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int k = 0; k < kPsi; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + w];
-    __syncthreads();
+// Psi_S = sum of psi over the node's range, bottom-up in one pass: a thread
+// per (leaf, value) sums the leaf's edges in order, then climbs; at each
+// parent the second of its two children to arrive (an agent-scope counter,
+// reset by that thread) writes Psi_parent = Psi_left + Psi_right, so every
+// sum has a fixed order whatever the arrival order.
+__global__ void k_bct_up(const int* __restrict__ leaf_node, int n_leaves, const int4* __restrict__ node,
+                         const int* __restrict__ parent, const double* __restrict__ psi, double* __restrict__ Psi,
+                         int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_leaves * kPsi) return;
+  const int k = i % kPsi;
+  int n = leaf_node[i / kPsi];
+  const int4 nd = node[n];
+  double a = 0.0;
+  for (int q = 0; q < nd.y; ++q) a += psi[(size_t)kPsi * (nd.x + q) + k];
+  Psi[(size_t)kPsi * n + k] = a;
+  for (;;) {
+    const int par = parent[n];
+    if (par < 0) return;
+    int* f = flag + (size_t)kPsi * par + k;
+    // release: this node's sum is visible before the count; acquire: the sibling's is visible after it
+    if (__hip_atomic_fetch_add(f, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+    __hip_atomic_store(f, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int c0 = node[par].z;
+    const double v = __hip_atomic_load(Psi + (size_t)kPsi * c0 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+                     __hip_atomic_load(Psi + (size_t)kPsi * (c0 + 1) + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(Psi + (size_t)kPsi * par + k, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    n = par;
   }
-  if (threadIdx.x < kPsi) Psi[(size_t)kPsi * blockIdx.x + threadIdx.x] = sm[threadIdx.x][0];
 }
 
 // The two kernels between tangent-points (x, T) and (y, U), d = x - y:
@@ -151,24 +163,33 @@ __global__ void k_bct_down(const int4* __restrict__ node, const double* __restri
   for (int k = 0; k < kPhi; ++k) phi[(size_t)kPhi * p + k] = l * a[k];
 }
 
-// Exact near blocks: one workgroup of 256 per target leaf T (at most 32 edges):
-// eight groups of 32 threads take the leaf's near source leaves in turn
-// (group j the blocks j, j + 8, ...), a thread per target edge, each group
-// staging its source leaf in its own LDS slice; the eight partial sums are
+// Exact near blocks.  A task is a target leaf T (at most 32 edges) with a
+// run of at most kTaskBlocks of its near source leaves; a leaf with a longer
+// near list is split over several tasks (workgroups), whose partial sums go
+// to their own slots and are added in task order afterwards.  Per round the
+// workgroup stages up to eight source leaves as one flat list of at most 256
+// source edges in LDS; a thread per target edge in each of eight groups of 32
+// sweeps its group's equal share of that list; the eight partial sums are
 // added in group order.
 constexpr int kNearGroups = 8;
+constexpr int kTaskRounds = 4;
+constexpr int kTaskBlocks = kNearGroups * kTaskRounds;
+constexpr int kStage = kNearGroups * 32;
+constexpr int kSrcVals = 6 + kPsi;  // x (3), T (3), psi
 template <int EC>
-__global__ __launch_bounds__(256) void k_bct_near(const int* __restrict__ near_off, const int* __restrict__ near_src,
+__global__ __launch_bounds__(256) void k_bct_near(const int4* __restrict__ task, const int* __restrict__ near_src,
                                                   const int* __restrict__ leaf_node, const int4* __restrict__ node,
                                                   const int* __restrict__ perm, const int2* __restrict__ edges,
                                                   const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GB,
                                                   const V4<double>* __restrict__ GT, const double* __restrict__ psi,
-                                                  double half_expo, double* __restrict__ phi) {
-  __shared__ double sx[kNearGroups][32][3], st[kNearGroups][32][3], sp[kNearGroups][32][kPsi];
-  __shared__ int2 se[kNearGroups][32];
-  __shared__ double red[kNearGroups][32][kPhi];
-  const int Tn = leaf_node[blockIdx.x];
-  const int4 tn = node[Tn];
+                                                  double half_expo, double* __restrict__ phi,
+                                                  double* __restrict__ part) {
+  static_assert(kNearGroups * 32 * kPhi <= kStage * kSrcVals, "the group sums reuse the staging memory");
+  __shared__ double sd[kStage * kSrcVals];
+  __shared__ int2 se[kStage];
+  __shared__ int soff[kNearGroups + 1], sbeg[kNearGroups];
+  const int4 tk = task[blockIdx.x];  // (leaf index, first block, end block, partial slot or -1)
+  const int4 tn = node[leaf_node[tk.x]];
   const int grp = threadIdx.x / 32, tid = threadIdx.x % 32;
   const bool act = tid < tn.y;
   const int p = tn.x + (act ? tid : 0);
@@ -178,48 +199,86 @@ __global__ __launch_bounds__(256) void k_bct_near(const int* __restrict__ near_o
   const int2 ei = edges[I];
   double acc[kPhi];
   for (int k = 0; k < kPhi; ++k) acc[k] = 0.0;
-  const int q0 = near_off[blockIdx.x], q1 = near_off[blockIdx.x + 1];
-  // every group runs the same number of rounds, so the barriers match
-  const int rounds = (q1 - q0 + kNearGroups - 1) / kNearGroups;
-  for (int r = 0; r < rounds; ++r) {
-    const int q = q0 + r * kNearGroups + grp;
-    const bool has = q < q1;
-    const int4 sn = has ? node[near_src[q]] : make_int4(0, 0, -1, 0);
-    __syncthreads();
-    if (tid < sn.y) {
-      const int pj = sn.x + tid;
-      const int J = perm[pj];
-      const V4<double> qa = GA[J], qb = GB[J], qt = GT[J];
-      sx[grp][tid][0] = 0.5 * (qa.x + qb.x);
-      sx[grp][tid][1] = 0.5 * (qa.y + qb.y);
-      sx[grp][tid][2] = 0.5 * (qa.z + qb.z);
-      st[grp][tid][0] = qt.x;
-      st[grp][tid][1] = qt.y;
-      st[grp][tid][2] = qt.z;
-      se[grp][tid] = edges[J];
-      for (int k = 0; k < kPsi; ++k) sp[grp][tid][k] = psi[(size_t)kPsi * pj + k];
+  for (int q = tk.y; q < tk.z; q += kNearGroups) {
+    const int nb = min(kNearGroups, tk.z - q);
+    __syncthreads();  // the previous round's list is no longer read
+    if (threadIdx.x == 0) {
+      int o = 0;
+      for (int j = 0; j < nb; ++j) {
+        const int4 sn = node[near_src[q + j]];
+        soff[j] = o;
+        sbeg[j] = sn.x;
+        o += sn.y;
+      }
+      soff[nb] = o;
     }
     __syncthreads();
+    const int m = soff[nb];  // <= 8 leaves of <= 32 edges
+    if ((int)threadIdx.x < m) {
+      int j = 0;
+      while ((int)threadIdx.x >= soff[j + 1]) ++j;
+      const int pj = sbeg[j] + (int)threadIdx.x - soff[j];
+      const int J = perm[pj];
+      const V4<double> qa = GA[J], qb = GB[J], qt = GT[J];
+      double* d = sd + kSrcVals * threadIdx.x;
+      d[0] = 0.5 * (qa.x + qb.x);
+      d[1] = 0.5 * (qa.y + qb.y);
+      d[2] = 0.5 * (qa.z + qb.z);
+      d[3] = qt.x;
+      d[4] = qt.y;
+      d[5] = qt.z;
+      for (int k = 0; k < kPsi; ++k) d[6 + k] = psi[(size_t)kPsi * pj + k];
+      se[threadIdx.x] = edges[J];
+    }
+    __syncthreads();
+    const int share = (m + kNearGroups - 1) / kNearGroups;
+    const int u1 = min(m, (grp + 1) * share);
     if (act)
-      for (int u = 0; u < sn.y; ++u) {
-        const int2 ej = se[grp][u];
+      for (int u = grp * share; u < u1; ++u) {
+        const int2 ej = se[u];
         if ((ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y)) continue;
+        const double* d = sd + kSrcVals * u;
         double klo, khi;
-        bct_kernels<EC>(x0 - sx[grp][u][0], x1 - sx[grp][u][1], x2 - sx[grp][u][2], t.x, t.y, t.z, st[grp][u][0],
-                        st[grp][u][1], st[grp][u][2], half_expo, klo, khi);
-        for (int k = 0; k < 4; ++k) acc[k] += klo * sp[grp][u][k];
-        acc[4] += khi * sp[grp][u][0];
-        for (int k = 0; k < 9; ++k) acc[5 + k] += khi * sp[grp][u][4 + k];
+        bct_kernels<EC>(x0 - d[0], x1 - d[1], x2 - d[2], t.x, t.y, t.z, d[3], d[4], d[5], half_expo, klo, khi);
+        for (int k = 0; k < 4; ++k) acc[k] += klo * d[6 + k];
+        acc[4] += khi * d[6];
+        for (int k = 0; k < 9; ++k) acc[5 + k] += khi * d[10 + k];
       }
   }
-  for (int k = 0; k < kPhi; ++k) red[grp][tid][k] = acc[k];
+  __syncthreads();
+  double* red = sd;  // [group][target][kPhi]
+  for (int k = 0; k < kPhi; ++k) red[(threadIdx.x) * kPhi + k] = acc[k];
   __syncthreads();
   if (grp == 0 && act) {
     for (int k = 0; k < kPhi; ++k) {
-      double v = red[0][tid][k];
-      for (int g = 1; g < kNearGroups; ++g) v += red[g][tid][k];
-      phi[(size_t)kPhi * p + k] += a.w * v;
+      double v = red[tid * kPhi + k];
+      for (int g = 1; g < kNearGroups; ++g) v += red[(g * 32 + tid) * kPhi + k];
+      if (tk.w < 0)
+        phi[(size_t)kPhi * p + k] += a.w * v;
+      else
+        part[((size_t)tk.w * 32 + tid) * kPhi + k] = v;
     }
+  }
+}
+
+// Leaves whose near list spans several tasks: phi += l_I (sum of the tasks'
+// partial sums, in task order).  red[r] = (leaf index, first slot, slots).
+__global__ void k_bct_near_sum(const int4* __restrict__ red, int n_red, const int* __restrict__ leaf_node,
+                               const int4* __restrict__ node, const int* __restrict__ perm,
+                               const V4<double>* __restrict__ GA, const double* __restrict__ part,
+                               double* __restrict__ phi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_red * 32) return;
+  const int4 r = red[i / 32];
+  const int tid = i % 32;
+  const int4 tn = node[leaf_node[r.x]];
+  if (tid >= tn.y) return;
+  const int p = tn.x + tid;
+  const double l = GA[perm[p]].w;
+  for (int k = 0; k < kPhi; ++k) {
+    double v = 0.0;
+    for (int j = 0; j < r.z; ++j) v += part[((size_t)(r.y + j) * 32 + tid) * kPhi + k];
+    phi[(size_t)kPhi * p + k] += l * v;
   }
 }
 
@@ -295,12 +354,13 @@ rc_status Bct::ensure(int nE_, int nodes_) {
 }
 
 void Bct::release() {
-  void* ps[] = {psi, phi, ev, Psi, Phi, far_off, far_src, near_off, near_src, leaf_node};
+  void* ps[] = {psi, phi, ev, Psi, Phi, part, far_off, far_src, near_off, near_src, leaf_node, parent, flag, task, red};
   for (void* p : ps)
     if (p) hipFree(p);
-  psi = phi = ev = Psi = Phi = nullptr;
-  far_off = far_src = near_off = near_src = leaf_node = nullptr;
-  nE = cap_nodes = n_far = n_near = n_leaves = 0;
+  psi = phi = ev = Psi = Phi = part = nullptr;
+  far_off = far_src = near_off = near_src = leaf_node = parent = flag = nullptr;
+  task = red = nullptr;
+  nE = cap_nodes = n_far = n_near = n_leaves = n_tasks = n_red = 0;
   near_pairs = 0;
   ready = false;
 }
@@ -350,7 +410,7 @@ rc_status build_bct(const Curve& c, Bvh& bvh, Bct& bct, double theta, int leaf, 
     }
     cur.swap(next);
   }
-  std::vector<int> foff(nn + 1, 0), fsrc, noff(1, 0), nsrc, lnode;
+  std::vector<int> foff(nn + 1, 0), fsrc, noff(1, 0), nsrc, lnode, parent(nn, -1);
   for (int T = 0; T < nn; ++T) {
     foff[T + 1] = foff[T] + (int)far[T].size();
     fsrc.insert(fsrc.end(), far[T].begin(), far[T].end());
@@ -358,19 +418,42 @@ rc_status build_bct(const Curve& c, Bvh& bvh, Bct& bct, double theta, int leaf, 
       lnode.push_back(T);
       nsrc.insert(nsrc.end(), nearl[T].begin(), nearl[T].end());
       noff.push_back((int)nsrc.size());
+    } else {
+      parent[node[T].z] = T;
+      parent[node[T].z + 1] = T;
     }
   }
+  // near tasks: leaves with more than kTaskBlocks near blocks first, split
+  // into runs with a partial slot each; then one task per remaining leaf
+  std::vector<int4> tasks, reds;
+  int slots = 0;
+  const int nl = (int)lnode.size();
+  for (int li = 0; li < nl; ++li) {
+    const int q0 = noff[li], q1 = noff[li + 1];
+    if (q1 - q0 <= kTaskBlocks) continue;
+    const int nt = (q1 - q0 + kTaskBlocks - 1) / kTaskBlocks;
+    reds.push_back(make_int4(li, slots, nt, 0));
+    for (int j = 0; j < nt; ++j)
+      tasks.push_back(make_int4(li, q0 + j * kTaskBlocks, std::min(q1, q0 + (j + 1) * kTaskBlocks), slots++));
+  }
+  for (int li = 0; li < nl; ++li)
+    if (noff[li + 1] > noff[li] && noff[li + 1] - noff[li] <= kTaskBlocks)
+      tasks.push_back(make_int4(li, noff[li], noff[li + 1], -1));
   RC_TRY(bct.ensure(c.nE, nn));
-  void* ps[] = {bct.far_off, bct.far_src, bct.near_off, bct.near_src, bct.leaf_node};
+  void* ps[] = {bct.far_off, bct.far_src, bct.near_off, bct.near_src, bct.leaf_node, bct.parent, bct.flag,
+                bct.task, bct.red, bct.part};
   for (void* p : ps)
     if (p) hipFree(p);
-  bct.far_off = bct.far_src = bct.near_off = bct.near_src = bct.leaf_node = nullptr;
-  auto up = [&](int** dst, const std::vector<int>& v) -> rc_status {
-    if (hipMalloc((void**)dst, sizeof(int) * std::max<size_t>(v.size(), 1)) != hipSuccess) {
+  bct.far_off = bct.far_src = bct.near_off = bct.near_src = bct.leaf_node = bct.parent = bct.flag = nullptr;
+  bct.task = bct.red = nullptr;
+  bct.part = nullptr;
+  auto up = [&](auto** dst, const auto& v) -> rc_status {
+    using T = typename std::decay_t<decltype(v)>::value_type;
+    if (hipMalloc((void**)dst, sizeof(T) * std::max<size_t>(v.size(), 1)) != hipSuccess) {
       set_error("allocation of the block lists failed");
       return RC_ERR_NOMEM;
     }
-    if (!v.empty()) RC_HIP(hipMemcpy(*dst, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice));
+    if (!v.empty()) RC_HIP(hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
     return RC_OK;
   };
   RC_TRY(up(&bct.far_off, foff));
@@ -378,10 +461,21 @@ rc_status build_bct(const Curve& c, Bvh& bvh, Bct& bct, double theta, int leaf, 
   RC_TRY(up(&bct.near_off, noff));
   RC_TRY(up(&bct.near_src, nsrc));
   RC_TRY(up(&bct.leaf_node, lnode));
+  RC_TRY(up(&bct.parent, parent));
+  RC_TRY(up(&bct.task, tasks));
+  RC_TRY(up(&bct.red, reds));
+  // the climbing counters start at zero and every product leaves them at zero
+  RC_TRY(up(&bct.flag, std::vector<int>((size_t)kPsi * nn, 0)));
+  if (hipMalloc((void**)&bct.part, sizeof(double) * kPhi * 32 * std::max(slots, 1)) != hipSuccess) {
+    set_error("allocation of the block lists failed");
+    return RC_ERR_NOMEM;
+  }
   bct.n_nodes = nn;
   bct.n_far = (int)fsrc.size();
   bct.n_near = (int)nsrc.size();
-  bct.n_leaves = (int)lnode.size();
+  bct.n_leaves = nl;
+  bct.n_tasks = (int)tasks.size();
+  bct.n_red = (int)reds.size();
   bct.near_pairs = pairs;
   bct.theta = theta;
   bct.ready = true;
@@ -400,8 +494,9 @@ rc_status launch_bct_apply(const Curve& c, const Bvh& bvh, Bct& bct, double alph
   const V4<double>*GA = c.gd.a, *GB = c.gd.b, *GT = c.gd.t;
   hipLaunchKernelGGL(k_bct_rhs, dim3(bct_cdiv(nE, 256)), dim3(256), 0, s, X, (const int2*)c.edges, GA, GT,
                      (const int*)bvh.perm, nE, bct.psi);
-  hipLaunchKernelGGL(k_bct_node_sums, dim3(bct.n_nodes), dim3(256), 0, s, (const int4*)bvh.node,
-                     (const double*)bct.psi, bct.Psi);
+  hipLaunchKernelGGL(k_bct_up, dim3(bct_cdiv(bct.n_leaves * kPsi, 256)), dim3(256), 0, s, (const int*)bct.leaf_node,
+                     bct.n_leaves, (const int4*)bvh.node, (const int*)bct.parent, (const double*)bct.psi, bct.Psi,
+                     bct.flag);
   auto far_near = [&](auto ec) {
     constexpr int EC = decltype(ec)::value;
     hipLaunchKernelGGL((k_bct_far<EC>), dim3(bct_cdiv(bct.n_nodes, 4)), dim3(256), 0, s, (const int*)bct.far_off,
@@ -409,10 +504,15 @@ rc_status launch_bct_apply(const Curve& c, const Bvh& bvh, Bct& bct, double alph
                        (const double*)bct.Psi, bct.n_nodes, half_expo, bct.Phi);
     hipLaunchKernelGGL(k_bct_down, dim3(bct_cdiv(nE, 256)), dim3(256), 0, s, (const int4*)bvh.node,
                        (const double*)bct.Phi, GA, (const int*)bvh.perm, nE, bct.phi);
-    hipLaunchKernelGGL((k_bct_near<EC>), dim3(bct.n_leaves), dim3(256), 0, s, (const int*)bct.near_off,
-                       (const int*)bct.near_src, (const int*)bct.leaf_node, (const int4*)bvh.node,
-                       (const int*)bvh.perm, (const int2*)c.edges, GA, GB, GT, (const double*)bct.psi, half_expo,
-                       bct.phi);
+    if (bct.n_tasks > 0)
+      hipLaunchKernelGGL((k_bct_near<EC>), dim3(bct.n_tasks), dim3(256), 0, s, (const int4*)bct.task,
+                         (const int*)bct.near_src, (const int*)bct.leaf_node, (const int4*)bvh.node,
+                         (const int*)bvh.perm, (const int2*)c.edges, GA, GB, GT, (const double*)bct.psi, half_expo,
+                         bct.phi, bct.part);
+    if (bct.n_red > 0)
+      hipLaunchKernelGGL(k_bct_near_sum, dim3(bct_cdiv(bct.n_red * 32, 256)), dim3(256), 0, s, (const int4*)bct.red,
+                         bct.n_red, (const int*)bct.leaf_node, (const int4*)bvh.node, (const int*)bvh.perm, GA,
+                         (const double*)bct.part, bct.phi);
   };
   switch (exp_case(alpha, beta)) {
     case kA2B4: far_near(std::integral_constant<int, kA2B4>{}); break;
