@@ -61,34 +61,30 @@ __global__ void k_bct_rhs(const double* __restrict__ X, const int2* __restrict__
   }
 }
 
-// Psi_S = sum of psi over the node's range, bottom-up in one pass: a thread
-// per (leaf, value) sums the leaf's edges in order, then climbs; at each
-// parent the second of its two children to arrive (an agent-scope counter,
-// reset by that thread) writes Psi_parent = Psi_left + Psi_right, so every
-// sum has a fixed order whatever the arrival order.
-__global__ void k_bct_up(const int* __restrict__ leaf_node, int n_leaves, const int4* __restrict__ node,
-                         const int* __restrict__ parent, const double* __restrict__ psi, double* __restrict__ Psi,
-                         int* __restrict__ flag) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_leaves * kPsi) return;
-  const int k = i % kPsi;
-  int n = leaf_node[i / kPsi];
-  const int4 nd = node[n];
-  double a = 0.0;
-  for (int q = 0; q < nd.y; ++q) a += psi[(size_t)kPsi * (nd.x + q) + k];
-  Psi[(size_t)kPsi * n + k] = a;
-  for (;;) {
-    const int par = parent[n];
-    if (par < 0) return;
-    int* f = flag + (size_t)kPsi * par + k;
-    // release: this node's sum is visible before the count; acquire: the sibling's is visible after it
-    if (__hip_atomic_fetch_add(f, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
-    __hip_atomic_store(f, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int c0 = node[par].z;
-    const double v = __hip_atomic_load(Psi + (size_t)kPsi * c0 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-                     __hip_atomic_load(Psi + (size_t)kPsi * (c0 + 1) + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(Psi + (size_t)kPsi * par + k, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    n = par;
+// Psi_S = sum of psi over the node's range, bottom-up: a leaf sums its edges
+// in order, an internal node adds its two children (left + right).  The
+// schedule is built with the tree: the nodes of each subtree below a cut depth
+// go to one workgroup, deepest first, one segment per depth (a barrier
+// between segments); the nodes above the cut are a last workgroup of their own,
+// run by a second launch.
+__global__ __launch_bounds__(256) void k_bct_sums(const int* __restrict__ wseg, const int2* __restrict__ seg,
+                                                  const int* __restrict__ ord, int w0, const int4* __restrict__ node,
+                                                  const double* __restrict__ psi, double* __restrict__ Psi) {
+  const int w = w0 + blockIdx.x;
+  for (int g = wseg[w]; g < wseg[w + 1]; ++g) {
+    const int2 sg = seg[g];
+    const int items = (sg.y - sg.x) * kPsi;
+    for (int i = threadIdx.x; i < items; i += blockDim.x) {
+      const int n = ord[sg.x + i / kPsi], k = i % kPsi;
+      const int4 nd = node[n];
+      double a = 0.0;
+      if (nd.z < 0)
+        for (int q = 0; q < nd.y; ++q) a += psi[(size_t)kPsi * (nd.x + q) + k];
+      else
+        a = Psi[(size_t)kPsi * nd.z + k] + Psi[(size_t)kPsi * (nd.z + 1) + k];
+      Psi[(size_t)kPsi * n + k] = a;
+    }
+    __syncthreads();  // this depth's sums are read by the next segment
   }
 }
 
@@ -277,7 +273,15 @@ __global__ void k_bct_near_sum(const int4* __restrict__ red, int n_red, const in
   const double l = GA[perm[p]].w;
   for (int k = 0; k < kPhi; ++k) {
     double v = 0.0;
-    for (int j = 0; j < r.z; ++j) v += part[((size_t)(r.y + j) * 32 + tid) * kPhi + k];
+    int j = 0;
+    for (; j + 8 <= r.z; j += 8) {  // eight loads in flight, added in slot order
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = part[((size_t)(r.y + j + u) * 32 + tid) * kPhi + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += t[u];
+    }
+    for (; j < r.z; ++j) v += part[((size_t)(r.y + j) * 32 + tid) * kPhi + k];
     phi[(size_t)kPhi * p + k] += l * v;
   }
 }
@@ -354,13 +358,14 @@ rc_status Bct::ensure(int nE_, int nodes_) {
 }
 
 void Bct::release() {
-  void* ps[] = {psi, phi, ev, Psi, Phi, part, far_off, far_src, near_off, near_src, leaf_node, parent, flag, task, red};
+  void* ps[] = {psi, phi, ev, Psi, Phi, part, far_off, far_src, near_off, near_src, leaf_node, wseg, ord, task, red, seg};
   for (void* p : ps)
     if (p) hipFree(p);
   psi = phi = ev = Psi = Phi = part = nullptr;
-  far_off = far_src = near_off = near_src = leaf_node = parent = flag = nullptr;
+  far_off = far_src = near_off = near_src = leaf_node = wseg = ord = nullptr;
   task = red = nullptr;
-  nE = cap_nodes = n_far = n_near = n_leaves = n_tasks = n_red = 0;
+  seg = nullptr;
+  nE = cap_nodes = n_far = n_near = n_leaves = n_tasks = n_red = n_sub = 0;
   near_pairs = 0;
   ready = false;
 }
@@ -410,7 +415,7 @@ rc_status build_bct(const Curve& c, Bvh& bvh, Bct& bct, double theta, int leaf, 
     }
     cur.swap(next);
   }
-  std::vector<int> foff(nn + 1, 0), fsrc, noff(1, 0), nsrc, lnode, parent(nn, -1);
+  std::vector<int> foff(nn + 1, 0), fsrc, noff(1, 0), nsrc, lnode;
   for (int T = 0; T < nn; ++T) {
     foff[T + 1] = foff[T] + (int)far[T].size();
     fsrc.insert(fsrc.end(), far[T].begin(), far[T].end());
@@ -418,10 +423,40 @@ rc_status build_bct(const Curve& c, Bvh& bvh, Bct& bct, double theta, int leaf, 
       lnode.push_back(T);
       nsrc.insert(nsrc.end(), nearl[T].begin(), nearl[T].end());
       noff.push_back((int)nsrc.size());
-    } else {
-      parent[node[T].z] = T;
-      parent[node[T].z + 1] = T;
     }
+  }
+  // node-sum schedule: depths (children follow their parents in node order),
+  // the cut at the first depth with at least 256 nodes, one workgroup per
+  // subtree below it and a last one for the nodes above it
+  std::vector<int> depth(nn, 0), sub(nn, -1), per_depth;
+  for (int T = 0; T < nn; ++T) {
+    if ((int)per_depth.size() <= depth[T]) per_depth.resize(depth[T] + 1, 0);
+    ++per_depth[depth[T]];
+    if (node[T].z >= 0) depth[node[T].z] = depth[node[T].z + 1] = depth[T] + 1;
+  }
+  const int maxd = (int)per_depth.size() - 1;
+  int cut = maxd + 1;
+  for (int d = 0; d <= maxd; ++d)
+    if (per_depth[d] >= 256) {
+      cut = d;
+      break;
+    }
+  int nsub = 0;
+  for (int T = 0; T < nn; ++T) {
+    if (depth[T] == cut) sub[T] = nsub++;
+    if (node[T].z >= 0 && sub[T] >= 0) sub[node[T].z] = sub[node[T].z + 1] = sub[T];
+  }
+  std::vector<std::vector<std::vector<int>>> by(nsub + 1, std::vector<std::vector<int>>(maxd + 1));
+  for (int T = 0; T < nn; ++T) by[sub[T] >= 0 ? sub[T] : nsub][depth[T]].push_back(T);
+  std::vector<int> wseg(1, 0), ord;
+  std::vector<int2> segs;
+  for (int w = 0; w <= nsub; ++w) {
+    for (int d = maxd; d >= 0; --d)
+      if (!by[w][d].empty()) {
+        segs.push_back(make_int2((int)ord.size(), (int)(ord.size() + by[w][d].size())));
+        ord.insert(ord.end(), by[w][d].begin(), by[w][d].end());
+      }
+    wseg.push_back((int)segs.size());
   }
   // near tasks: leaves with more than kTaskBlocks near blocks first, split
   // into runs with a partial slot each; then one task per remaining leaf
@@ -440,12 +475,13 @@ rc_status build_bct(const Curve& c, Bvh& bvh, Bct& bct, double theta, int leaf, 
     if (noff[li + 1] > noff[li] && noff[li + 1] - noff[li] <= kTaskBlocks)
       tasks.push_back(make_int4(li, noff[li], noff[li + 1], -1));
   RC_TRY(bct.ensure(c.nE, nn));
-  void* ps[] = {bct.far_off, bct.far_src, bct.near_off, bct.near_src, bct.leaf_node, bct.parent, bct.flag,
-                bct.task, bct.red, bct.part};
+  void* ps[] = {bct.far_off, bct.far_src, bct.near_off, bct.near_src, bct.leaf_node, bct.wseg, bct.ord,
+                bct.task, bct.red, bct.part, bct.seg};
   for (void* p : ps)
     if (p) hipFree(p);
-  bct.far_off = bct.far_src = bct.near_off = bct.near_src = bct.leaf_node = bct.parent = bct.flag = nullptr;
+  bct.far_off = bct.far_src = bct.near_off = bct.near_src = bct.leaf_node = bct.wseg = bct.ord = nullptr;
   bct.task = bct.red = nullptr;
+  bct.seg = nullptr;
   bct.part = nullptr;
   auto up = [&](auto** dst, const auto& v) -> rc_status {
     using T = typename std::decay_t<decltype(v)>::value_type;
@@ -461,11 +497,12 @@ rc_status build_bct(const Curve& c, Bvh& bvh, Bct& bct, double theta, int leaf, 
   RC_TRY(up(&bct.near_off, noff));
   RC_TRY(up(&bct.near_src, nsrc));
   RC_TRY(up(&bct.leaf_node, lnode));
-  RC_TRY(up(&bct.parent, parent));
   RC_TRY(up(&bct.task, tasks));
   RC_TRY(up(&bct.red, reds));
-  // the climbing counters start at zero and every product leaves them at zero
-  RC_TRY(up(&bct.flag, std::vector<int>((size_t)kPsi * nn, 0)));
+  RC_TRY(up(&bct.wseg, wseg));
+  RC_TRY(up(&bct.seg, segs));
+  RC_TRY(up(&bct.ord, ord));
+  bct.n_sub = nsub;
   if (hipMalloc((void**)&bct.part, sizeof(double) * kPhi * 32 * std::max(slots, 1)) != hipSuccess) {
     set_error("allocation of the block lists failed");
     return RC_ERR_NOMEM;
@@ -494,9 +531,11 @@ rc_status launch_bct_apply(const Curve& c, const Bvh& bvh, Bct& bct, double alph
   const V4<double>*GA = c.gd.a, *GB = c.gd.b, *GT = c.gd.t;
   hipLaunchKernelGGL(k_bct_rhs, dim3(bct_cdiv(nE, 256)), dim3(256), 0, s, X, (const int2*)c.edges, GA, GT,
                      (const int*)bvh.perm, nE, bct.psi);
-  hipLaunchKernelGGL(k_bct_up, dim3(bct_cdiv(bct.n_leaves * kPsi, 256)), dim3(256), 0, s, (const int*)bct.leaf_node,
-                     bct.n_leaves, (const int4*)bvh.node, (const int*)bct.parent, (const double*)bct.psi, bct.Psi,
-                     bct.flag);
+  if (bct.n_sub > 0)
+    hipLaunchKernelGGL(k_bct_sums, dim3(bct.n_sub), dim3(256), 0, s, (const int*)bct.wseg, (const int2*)bct.seg,
+                       (const int*)bct.ord, 0, (const int4*)bvh.node, (const double*)bct.psi, bct.Psi);
+  hipLaunchKernelGGL(k_bct_sums, dim3(1), dim3(256), 0, s, (const int*)bct.wseg, (const int2*)bct.seg,
+                     (const int*)bct.ord, bct.n_sub, (const int4*)bvh.node, (const double*)bct.psi, bct.Psi);
   auto far_near = [&](auto ec) {
     constexpr int EC = decltype(ec)::value;
     hipLaunchKernelGGL((k_bct_far<EC>), dim3(bct_cdiv(bct.n_nodes, 4)), dim3(256), 0, s, (const int*)bct.far_off,

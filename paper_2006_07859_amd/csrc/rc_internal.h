@@ -255,15 +255,16 @@ struct Bvh {
 // hierarchical product and the block lists (far blocks per target node,
 // near source leaves per target leaf).
 struct Bct {
-  int nE = 0, cap_nodes = 0, n_nodes = 0, n_far = 0, n_near = 0, n_leaves = 0, n_tasks = 0, n_red = 0;
+  int nE = 0, cap_nodes = 0, n_nodes = 0, n_far = 0, n_near = 0, n_leaves = 0, n_tasks = 0, n_red = 0, n_sub = 0;
   long long near_pairs = 0;
   double theta = 0.0;
   bool ready = false;
   double *psi = nullptr, *phi = nullptr, *ev = nullptr, *Psi = nullptr, *Phi = nullptr;
   double* part = nullptr;  // partial near sums of leaves split over several tasks
   int *far_off = nullptr, *far_src = nullptr, *near_off = nullptr, *near_src = nullptr, *leaf_node = nullptr;
-  int *parent = nullptr, *flag = nullptr;  // BVH parents and the bottom-up sweep's counters
-  int4 *task = nullptr, *red = nullptr;    // near tasks and the split leaves' partial-sum runs
+  int *wseg = nullptr, *ord = nullptr;  // node-sum schedule: segments per workgroup, nodes per segment
+  int2* seg = nullptr;
+  int4 *task = nullptr, *red = nullptr;  // near tasks and the split leaves' partial-sum runs
   rc_status ensure(int nE_, int nodes_);
   void release();
 };
