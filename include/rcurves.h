@@ -91,10 +91,11 @@ typedef enum {
   RC_SOLVE_DENSE = 0,    /* assembled FP64 A, Cholesky of Abar + C^T C, Schur complement */
   RC_SOLVE_PCG_JACOBI = 1, /* matrix-free projected PCG, Jacobi preconditioner */
   RC_SOLVE_PCG_MG = 2,   /* matrix-free projected PCG, multigrid V-cycle preconditioner */
-  RC_SOLVE_PCG_MULTILEVEL = 3, /* additive multilevel preconditioner sum_l P_l D_l P_l^T over the
-                                  multigrid levels, D_l = diag(A_l)^-1 (hand-weighted) */
-  RC_SOLVE_PCG_LEARNED = 4     /* the same with D_l = diag(y_l / diag(A_l)), y_l from the MLP attached
-                                  by rc_learned_attach */
+  RC_SOLVE_PCG_LEARNED = 4 /* the multigrid V-cycle with learned smoother weights: the MLP attached by
+                              rc_learned_attach predicts a diagonal scaling per vertex that places the
+                              top of the smoother's spectrum at 1, which fixes the Chebyshev interval (no
+                              spectral estimate); one closed loop numbered along itself.  (The value 3
+                              is not a solver kind.) */
 } rc_solver;
 
 typedef struct {
@@ -495,12 +496,20 @@ rc_status rc_batch_sobolev_apply(rc_ctx* ctx, const double* gamma, const double*
 rc_status rc_batch_pcg_state(rc_ctx* ctx, double* iters_h, double* res_h);
 
 /* ------------------------------------------------------------------------
- * Learned multilevel preconditioner.  For a single closed loop whose
- * vertices are numbered along it, M^-1 = sum_l P_l D_l P_l^T over the
- * multigrid levels (the black/white hierarchy of App. B.3.1, P_l the chained
- * prolongations), with D_l = diag(y_{l,v} / diag(A_l)_v) and y > 0 the output
- * of an MLP (8 -> 64 -> 64 -> 1, ReLU, softplus) on per-vertex features.
- * Symmetric positive definite for any weights; PCG applies P M^-1 P.
+ * Learned smoother weights of the multigrid V-cycle (App. B.3.1 hierarchy;
+ * the learned part is not in the paper).  For a single closed loop whose
+ * vertices are numbered along it, an MLP (8 -> 64 -> 64 -> 1, ReLU,
+ * softplus) maps per-vertex features of every smoothed level l to
+ * p_v = 1 + y_v, a prediction of T_v = r_v lambda_l with
+ * r_v = sum_w |A_l,vw| / A_l,vv and lambda_l the largest eigenvalue of
+ * diag(r_v A_l,vv)^-1 A_l (<= 1 by Gershgorin), so that diag(T_v A_l,vv)^-1
+ * A_l tops out at exactly 1.  The smoother uses the diagonal
+ * D_v = 1.05 p_v A_l,vv and the Chebyshev interval [0.2, 1] without the power
+ * iteration of RC_SOLVE_PCG_MG; its degree-2 polynomial still damps
+ * eigenvalues up to 1.2, so predictions low by up to ~14% keep it
+ * convergent.  The V-cycle stays linear and symmetric, so PCG applies;
+ * RC_SOLVE_PCG_LEARNED falls back to RC_SOLVE_PCG_MG when its residual keeps
+ * growing (fallback_after).
  * ---------------------------------------------------------------------- */
 
 /* Number of MLP parameters (4,801), flat order W1 [8][64], b1 [64],
@@ -524,8 +533,8 @@ rc_status rc_mlp_backward(rc_mlp* mlp, const float* X, int32_t N, const float* d
  * (device float[n_params]) and learning rate lr > 0. */
 rc_status rc_mlp_adam(rc_mlp* mlp, const float* grad, float lr);
 
-/* Attaches mlp (NULL detaches) to the context for RC_SOLVE_PCG_LEARNED and
- * the rc_learned_* calls; the caller keeps ownership. */
+/* Attaches mlp (NULL detaches) to the context for RC_SOLVE_PCG_LEARNED; the
+ * caller keeps ownership. */
 rc_status rc_learned_attach(rc_ctx* ctx, rc_mlp* mlp);
 
 /* Level sizes of the hierarchy for coarsest size n_min (sizes_h: host
@@ -538,22 +547,21 @@ rc_status rc_learned_levels(rc_ctx* ctx, int32_t n_min, int32_t* sizes_h, int32_
  * closed loop numbered along itself. */
 rc_status rc_learned_features(rc_ctx* ctx, const double* gamma, int32_t n_min, float* X, double* diag);
 
-/* The scalings D_l (device double[N], levels stacked) at gamma: y / diag with
- * y from the attached MLP, or 1 / diag without one. */
-rc_status rc_learned_scalings(rc_ctx* ctx, const double* gamma, int32_t n_min, double* scal);
+/* Training targets at gamma: R device float[N] (levels stacked as for
+ * rc_learned_features), T_v = r_v lambda_l from each level's dense FP64
+ * operator (assembled in a temporary buffer of nV^2 doubles; nV <= 16,384),
+ * lambda_l the Rayleigh quotient after 60 power steps from the alternating
+ * vector (a lower bound, within ~0.5% here).  Synchronises the stream. */
+rc_status rc_learned_targets(rc_ctx* ctx, const double* gamma, int32_t n_min, float* R);
 
-/* Y = P M^-1 P X at gamma (device double[nV][3]); the constraints must be set. */
-rc_status rc_learned_apply(rc_ctx* ctx, const double* gamma, int32_t n_min, const double* X, double* Y);
-
-/* One training sample: loss = 1 - <z, g>_A^2 / (|z|_A^2 |g|_A^2) with
- * z = P M^-1 P dE and g = g_ref the projected gradient (the relative A-norm
- * error of the best-scaled application), its gradient through the MLP
- * (written to grad, device float[n_params], when grad is not NULL) and, when
- * lr > 0, one Adam step of the attached MLP.  A is the matrix-free FP32
- * operator; the constraints must be set.  gamma, dE, g_ref: device
- * double[nV][3]; *loss_h receives the loss.  Synchronises the stream. */
-rc_status rc_learned_train_step(rc_ctx* ctx, const double* gamma, const double* dE, const double* g_ref,
-                                int32_t n_min, float lr, double* loss_h, float* grad);
+/* One regression step of the MLP on rows X (device float[N][8]) with targets
+ * R (device float[N], > 1): p = 1 + y(X), loss = mean of
+ * w (log p - log R)^2 with w = 4 where p < R (an interval short of the
+ * spectrum) and 1 elsewhere; *loss_h receives the loss before the step, grad (optional,
+ * device float[n_params]) its gradient, and lr > 0 takes one Adam step
+ * (lr = 0: none).  Synchronises the MLP's stream. */
+rc_status rc_mlp_fit_step(rc_mlp* mlp, const float* X, const float* R, int32_t N, float lr, double* loss_h,
+                          float* grad);
 
 /* Kernel timing with HIP events on the context's stream.  rc_profile_enable
  * clears earlier records and, when enable != 0, brackets every launch of the

@@ -1,28 +1,28 @@
-"""Learned multilevel preconditioner, in float64 (oracle).
+"""Learned smoother weights of the multigrid V-cycle, in float64 (oracle).
 
 Test infrastructure only (see the package docstring).
 
 Not a construction of the paper.  It reuses the paper's multigrid hierarchy
 (App. B.3.1: black/white coarsening of a closed curve, keeping every other
-vertex, with prolongation J that copies kept vertices and averages the two
-kept neighbours of a removed one) and forms the additive preconditioner
+vertex) and its Jacobi-type smoothing, and learns the smoother's diagonal.
+For the operator A_l of Sec. 4.2 rediscretised on level l, the ratio
 
-    M^-1 = sum_l P_l D_l P_l^T,   P_0 = Id,  P_l = J_1 ... J_l,
+    r_v = sum_w |A_l,vw| / A_l,vv   (>= 2: A annihilates constants)
 
-with positive diagonal scalings ``D_l = diag(y_{l,v} / diag(A_l)_v)``, where
-A_l is the Sobolev operator of Sec. 4.2 rediscretised on level l and
-``y_{l,v} > 0`` is the output of a small MLP (3 layers, width 64, ReLU, softplus
-output) evaluated on per-vertex features.  ``y = 1`` is the hand-weighted
-(Jacobi-scaled) multilevel preconditioner.  M^-1 is symmetric positive
-definite for any parameters, and PCG applies it as ``P M^-1 P``.
+makes D_r = diag(r_v A_l,vv) a Gershgorin bound (the spectrum of D_r^-1 A_l
+lies in [0, 1]); with lambda_l its largest eigenvalue, the target
 
-Training minimises the relative A-norm error of one application to the
-right-hand side of the projected gradient problem (eq.
-GradientSaddlePointProblem), with g the exact projected gradient and the
-application scaled by the best factor c (PCG does not see the scale of M):
+    T_v = r_v lambda_l
 
-    loss = min_c |c z - g|_A^2 / |g|_A^2 = 1 - <z, g>_A^2 / (|z|_A^2 |g|_A^2),
-    z = P M^-1 P dE,  <x, y>_A = x^T Abar y.
+gives D = diag(T_v A_l,vv) whose D^-1 A_l tops out at exactly 1, so a
+Chebyshev smoother on D^-1 A_l (and on its projected forms, whose spectra lie
+inside) may take the fixed interval [frac, 1] instead of estimating the
+largest eigenvalue.  A small MLP (3 layers, width 64, ReLU, softplus output)
+maps per-vertex features to p = 1 + y and is trained by regression on T in
+log space, with under-prediction (p < T, where the interval would fall short
+of the spectrum) weighted by UNDER:
+
+    loss = mean_v w_v (log p_v - log T_v)^2,   w_v = UNDER if p_v < T_v else 1.
 
 Curves are single closed loops whose vertices are numbered along the loop.
 """
@@ -33,12 +33,12 @@ import numpy as np
 
 from . import sobolev, tpe
 
-__all__ = ["N_FEATURES", "WIDTH", "n_params", "init_params", "unpack", "forward", "backward", "adam_step",
-           "hierarchy", "features", "level_diagonals", "apply_multilevel", "loss_and_grad"]
+__all__ = ["N_FEATURES", "WIDTH", "UNDER", "n_params", "init_params", "unpack", "forward", "backward", "adam_step",
+           "hierarchy", "features", "level_diagonals", "level_operators", "l1_ratios", "targets", "fit_loss_and_grad"]
 
 N_FEATURES = 8
 WIDTH = 64
-OFFSET = 4  # vertices at most this far apart along the loop are not "other parts" of the curve
+UNDER = 4.0  # weight of an under-predicted ratio in the regression loss
 
 
 def n_params(f_in=N_FEATURES, width=WIDTH):
@@ -57,14 +57,15 @@ def unpack(theta, f_in=N_FEATURES, width=WIDTH):
     return out
 
 
-def init_params(seed=0, f_in=N_FEATURES, width=WIDTH):
+def init_params(seed=0, f_in=N_FEATURES, width=WIDTH, y0=1.7):
     """He-scaled hidden layers, a small output layer and an output bias with
-    softplus(b3) = 1, so that the network starts at the hand-weighted scalings."""
+    softplus(b3) = y0, so that the network starts near the constant ratio
+    1 + y0."""
     rng = np.random.default_rng(seed)
     W1 = rng.normal(0.0, np.sqrt(2.0 / f_in), size=(f_in, width))
     W2 = rng.normal(0.0, np.sqrt(2.0 / width), size=(width, width))
     W3 = rng.normal(0.0, 0.01, size=width)
-    b3 = np.array([np.log(np.e - 1.0)])
+    b3 = np.array([np.log(np.expm1(y0))])
     return np.concatenate([W1.ravel(), np.zeros(width), W2.ravel(), np.zeros(width), W3, b3])
 
 
@@ -139,19 +140,39 @@ def _loop_edges(n):
     return np.stack([np.arange(n), (np.arange(n) + 1) % n], axis=1)
 
 
+def level_operators(gammas, alpha, beta):
+    """Dense A_l = B + B0 (Sec. 4.2, trapezoid weights) of every level."""
+    return [sum(sobolev.assemble(g, _loop_edges(len(g)), alpha, beta)) for g in gammas]
+
+
 def level_diagonals(gammas, alpha, beta):
-    return [np.diag(sum(sobolev.assemble(g, _loop_edges(len(g)), alpha, beta))) for g in gammas]
+    return [np.diag(A) for A in level_operators(gammas, alpha, beta)]
+
+
+def l1_ratios(As):
+    """r_v = sum_w |A_vw| / A_vv of every level, stacked finest first."""
+    return np.concatenate([np.abs(A).sum(1) / np.diag(A) for A in As])
+
+
+def targets(As):
+    """T_v = r_v lambda_l of every level (lambda_l the largest eigenvalue of
+    D_r^-1/2 A_l D_r^-1/2), stacked finest first."""
+    out = []
+    for A in As:
+        r = np.abs(A).sum(1) / np.diag(A)
+        s = 1.0 / np.sqrt(r * np.diag(A))
+        lam = np.linalg.eigvalsh(s[:, None] * A * s[None, :])[-1]
+        out.append(r * lam)
+    return np.concatenate(out)
 
 
 def features(gammas, diags):
     """Per-vertex features of every level, stacked level by level:
-    level / (levels - 1); log of the mean incident edge length over the level's
-    mean; turning angle; unit vertex tangent (3); log of the diagonal of A_l over
-    its mean; log of the distance to the nearest vertex more than OFFSET steps
-    away along the loop over the mean incident edge length."""
-    L = len(gammas)
+    log2(n_l) / 16; log of the mean incident edge length over the level's
+    mean; turning angle; unit vertex tangent (3); log of the diagonal of A_l
+    over its mean; log of the incoming over the outgoing edge length."""
     rows = []
-    for l, (g, dg) in enumerate(zip(gammas, diags)):
+    for g, dg in zip(gammas, diags):
         n = len(g)
         ell, T, _ = tpe.edge_geometry(g, _loop_edges(n))
         lin, Tin = np.roll(ell, 1), np.roll(T, 1, axis=0)   # edge into v, and out of v
@@ -159,59 +180,24 @@ def features(gammas, diags):
         turn = np.arccos(np.clip((Tin * T).sum(1), -1.0, 1.0))
         tv = Tin + T
         tv /= np.linalg.norm(tv, axis=1)[:, None]
-        d = np.linalg.norm(g[:, None, :] - g[None, :, :], axis=2)
-        idx = np.arange(n)
-        sep = np.abs(idx[:, None] - idx[None, :])
-        sep = np.minimum(sep, n - sep)
-        d[sep <= OFFSET] = np.inf
         F = np.empty((n, N_FEATURES))
-        F[:, 0] = l / max(1, L - 1)
+        F[:, 0] = np.log2(n) / 16.0
         F[:, 1] = np.log(lbar / ell.mean())
         F[:, 2] = turn
         F[:, 3:6] = tv
         F[:, 6] = np.log(dg / dg.mean())
-        F[:, 7] = np.log(d.min(1) / lbar)
+        F[:, 7] = np.log(lin / ell)
         rows.append(F)
     return np.concatenate(rows)
 
 
-def apply_multilevel(Js, scal, r):
-    """sum_l P_l diag(scal_l) P_l^T r for r [n0, 3]; scal is the list of
-    per-level vertex scalings (D_l)."""
-    us = [np.asarray(r, dtype=np.float64)]
-    for J in Js:
-        us.append(J.T @ us[-1])
-    z = scal[-1][:, None] * us[-1]
-    for l in range(len(Js) - 1, -1, -1):
-        z = scal[l][:, None] * us[l] + Js[l] @ z
-    return z
-
-
-def loss_and_grad(theta, gamma, dE, g_ref, A, C, alpha, beta, n_min=256):
-    """Relative A-norm error of the best-scaled P M^-1 P dE against the
-    projected gradient g_ref, and its gradient with respect to the parameters."""
-    gammas, Js = hierarchy(gamma, n_min)
-    diags = level_diagonals(gammas, alpha, beta)
-    X = features(gammas, diags)
+def fit_loss_and_grad(theta, X, R):
+    """The regression loss of p = 1 + y(X) on the targets R and its gradient
+    with respect to the parameters."""
     y, cache = forward(theta, X)
-    sizes = [len(g) for g in gammas]
-    cuts = np.cumsum([0] + sizes)
-    scal = [y[cuts[l]:cuts[l + 1]] / diags[l] for l in range(len(sizes))]
-    P = np.eye(C.shape[1]) - C.T @ np.linalg.solve(C @ C.T, C)
-    Pd = (P @ np.asarray(dE).ravel()).reshape(-1, 3)
-    z = (P @ apply_multilevel(Js, scal, Pd).ravel()).reshape(-1, 3)
-    Ab = np.kron(A, np.eye(3))
-    gr = np.asarray(g_ref).ravel()
-    zr = z.ravel()
-    Az, Ag = Ab @ zr, Ab @ gr
-    a, b, c = zr @ Ag, zr @ Az, gr @ Ag
-    loss = 1.0 - a * a / (b * c)
-    w = (P @ ((2.0 * a / (b * c)) * ((a / b) * Az - Ag))).reshape(-1, 3)
-    # d loss / d scal_l[v] = sum_c (P_l^T w)[v, c] (P_l^T P dE)[v, c]
-    us, ws = [Pd], [w]
-    for J in Js:
-        us.append(J.T @ us[-1])
-        ws.append(J.T @ ws[-1])
-    dscal = [(ws[l] * us[l]).sum(1) for l in range(len(sizes))]
-    dy = np.concatenate([dscal[l] / diags[l] for l in range(len(sizes))])
+    p = 1.0 + y
+    e = np.log(p) - np.log(R)
+    w = np.where(p < R, UNDER, 1.0)
+    loss = float(np.mean(w * e * e))
+    dy = 2.0 * w * e / p / len(R)
     return loss, backward(theta, cache, dy)

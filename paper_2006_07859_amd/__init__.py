@@ -16,7 +16,6 @@ from ._lib import (  # noqa: F401
     RC_SOLVE_PCG_JACOBI,
     RC_SOLVE_PCG_LEARNED,
     RC_SOLVE_PCG_MG,
-    RC_SOLVE_PCG_MULTILEVEL,
     Batch,
     Context,
     Mlp,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "librcurves.so")
 
 RC_F64, RC_F32 = 0, 1
 RC_C_BARYCENTER, RC_C_TOTAL_LENGTH, RC_C_EDGE_LENGTH = 1, 2, 4
-RC_SOLVE_DENSE, RC_SOLVE_PCG_JACOBI, RC_SOLVE_PCG_MG, RC_SOLVE_PCG_MULTILEVEL, RC_SOLVE_PCG_LEARNED = 0, 1, 2, 3, 4
+RC_SOLVE_DENSE, RC_SOLVE_PCG_JACOBI, RC_SOLVE_PCG_MG, RC_SOLVE_PCG_LEARNED = 0, 1, 2, 4
 
 STATUS = {
     0: "RC_OK", 1: "RC_ERR_ARG", 2: "RC_ERR_PARAM_RANGE", 3: "RC_ERR_DEGENERATE", 4: "RC_ERR_NONFINITE",
@@ -36,7 +36,7 @@ EXPORTED = [
     "rc_batch_set_constraints", "rc_batch_gradient", "rc_batch_step", "rc_batch_pcg_state", "rc_batch_autotune",
     "rc_batch_sobolev_apply", "rc_mlp_n_params", "rc_mlp_create", "rc_mlp_destroy", "rc_mlp_get", "rc_mlp_set", "rc_mlp_forward",
     "rc_mlp_backward", "rc_mlp_adam", "rc_learned_attach", "rc_learned_levels", "rc_learned_features",
-    "rc_learned_scalings", "rc_learned_apply", "rc_learned_train_step", "rc_sync_status",
+    "rc_learned_targets", "rc_mlp_fit_step", "rc_sync_status",
     "rc_differential_noalloc", "rc_use_vertex_pairs", "rc_first_collision_time", "rc_bct_build", "rc_bct_stats",
     "rc_sobolev_apply_bct",
 ]
@@ -154,9 +154,8 @@ def load():
         "rc_sobolev_apply_bct": (I32, [P, P, P, P]),
         "rc_learned_levels": (I32, [P, I32, P, I32, C.POINTER(I32)]),
         "rc_learned_features": (I32, [P, P, I32, P, P]),
-        "rc_learned_scalings": (I32, [P, P, I32, P]),
-        "rc_learned_apply": (I32, [P, P, I32, P, P]),
-        "rc_learned_train_step": (I32, [P, P, P, P, I32, C.c_float, C.POINTER(D), P]),
+        "rc_learned_targets": (I32, [P, P, I32, P]),
+        "rc_mlp_fit_step": (I32, [P, P, P, I32, C.c_float, C.POINTER(D), P]),
     }
     for name, (res, args) in sig.items():
         if not hasattr(lib, name):
@@ -386,7 +385,7 @@ class Context:
         _check(load().rc_bh_last_work(self.h, C.byref(f), C.byref(n), C.byref(nodes), C.byref(depth)))
         return {"far": f.value, "near": n.value, "nodes": nodes.value, "depth": depth.value}
 
-    # learned multilevel preconditioner
+    # learned smoother weights of the V-cycle
     def rc_learned_attach(self, mlp):
         self._mlp = mlp  # the context does not own it: keep it alive
         _check(load().rc_learned_attach(self.h, None if mlp is None else mlp.h))
@@ -404,24 +403,12 @@ class Context:
                                           _ptr(X, (N, 8), torch.float32, "X"),
                                           None if diag is None else _ptr(diag, (N,), self._f64, "diag")))
 
-    def rc_learned_scalings(self, gamma, n_min, scal):
-        N = sum(self.rc_learned_levels(n_min))
-        _check(load().rc_learned_scalings(self.h, self._v(gamma, "gamma"), int(n_min),
-                                          _ptr(scal, (N,), self._f64, "scal")))
-
-    def rc_learned_apply(self, gamma, n_min, X, Y):
-        _check(load().rc_learned_apply(self.h, self._v(gamma, "gamma"), int(n_min), self._v(X, "X"),
-                                       self._v(Y, "Y")))
-
-    def rc_learned_train_step(self, gamma, dE, g_ref, n_min, lr, grad=None):
+    def rc_learned_targets(self, gamma, n_min, R):
         import torch
 
-        loss = C.c_double()
-        _check(load().rc_learned_train_step(self.h, self._v(gamma, "gamma"), self._v(dE, "dE"),
-                                            self._v(g_ref, "g_ref"), int(n_min), float(lr), C.byref(loss),
-                                            None if grad is None else _ptr(grad, (mlp_n_params(),), torch.float32,
-                                                                           "grad")))
-        return loss.value
+        N = sum(self.rc_learned_levels(n_min))
+        _check(load().rc_learned_targets(self.h, self._v(gamma, "gamma"), int(n_min),
+                                         _ptr(R, (N,), torch.float32, "R")))
 
 
 def mlp_n_params():
@@ -429,7 +416,7 @@ def mlp_n_params():
 
 
 class Mlp:
-    """Owns one rc_mlp (the network of the learned preconditioner) on the current stream."""
+    """Owns one rc_mlp (the network of the learned smoother weights) on the current stream."""
 
     def __init__(self, theta=None):
         lib = load()
@@ -484,6 +471,17 @@ class Mlp:
         import torch
 
         _check(load().rc_mlp_adam(self.h, _ptr(grad, (self.n,), torch.float32, "grad"), float(lr)))
+
+    def fit_step(self, X, R, lr, grad=None):
+        """One regression step on (X, R); returns the loss before the step."""
+        import torch
+
+        N = int(X.shape[0])
+        loss = C.c_double()
+        _check(load().rc_mlp_fit_step(self.h, _ptr(X, (N, 8), torch.float32, "X"), _ptr(R, (N,), torch.float32, "R"),
+                                      N, float(lr), C.byref(loss),
+                                      None if grad is None else _ptr(grad, (self.n,), torch.float32, "grad")))
+        return loss.value
 
 
 class Batch(Context):

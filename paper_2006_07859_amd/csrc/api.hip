@@ -895,39 +895,42 @@ extern "C" rc_status rc_learned_features(rc_ctx* c, const double* gamma, int32_t
   RC_TRY(check_ctx(c));
   RC_TRY(no_batch(c, "rc_learned_features"));
   RC_TRY(check_ptrs({gamma, X}));
-  RC_TRY(learn_prepare(c, gamma, n_min, false, false));
+  RC_TRY(learn_levels_at(c, gamma, n_min, true, nullptr));
   const int N = c->learn_N;
   RC_HIP(hipMemcpyAsync(X, c->learn_X, sizeof(float) * kMlpIn * N, hipMemcpyDeviceToDevice, c->stream));
   if (diag) RC_HIP(hipMemcpyAsync(diag, c->learn_diag, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
   return RC_OK;
 }
 
-extern "C" rc_status rc_learned_scalings(rc_ctx* c, const double* gamma, int32_t n_min, double* scal) {
+extern "C" rc_status rc_learned_targets(rc_ctx* c, const double* gamma, int32_t n_min, float* R) {
   RC_TRY(check_ctx(c));
-  RC_TRY(no_batch(c, "rc_learned_scalings"));
-  RC_TRY(check_ptrs({gamma, scal}));
-  RC_TRY(learn_prepare(c, gamma, n_min, c->mlp != nullptr, false));
-  RC_HIP(hipMemcpyAsync(scal, c->learn_scal, sizeof(double) * c->learn_N, hipMemcpyDeviceToDevice, c->stream));
-  return RC_OK;
+  RC_TRY(no_batch(c, "rc_learned_targets"));
+  RC_TRY(check_ptrs({gamma, R}));
+  return learn_levels_at(c, gamma, n_min, false, R);
 }
 
-extern "C" rc_status rc_learned_apply(rc_ctx* c, const double* gamma, int32_t n_min, const double* X, double* Y) {
-  RC_TRY(check_ctx(c));
-  RC_TRY(no_batch(c, "rc_learned_apply"));
-  RC_TRY(check_ptrs({gamma, X, Y}));
-  RC_TRY(cons_prepare(c, c->curve, c->cons, gamma));
-  RC_TRY(learn_prepare(c, gamma, n_min, c->mlp != nullptr, false));
-  return learn_apply(c, X, Y);
-}
-
-extern "C" rc_status rc_learned_train_step(rc_ctx* c, const double* gamma, const double* dE, const double* g_ref,
-                                           int32_t n_min, float lr, double* loss_h, float* grad) {
-  RC_TRY(check_ctx(c));
-  RC_TRY(no_batch(c, "rc_learned_train_step"));
-  RC_TRY(check_ptrs({gamma, dE, g_ref, loss_h}));
-  if (!(lr >= 0.f)) {
-    set_error("rc_learned_train_step: lr must be >= 0");
+extern "C" rc_status rc_mlp_fit_step(rc_mlp* m, const float* X, const float* R, int32_t N, float lr, double* loss_h,
+                                     float* grad) {
+  RC_TRY(check_mlp(m));
+  RC_TRY(check_ptrs({X, R, loss_h}));
+  if (N <= 0 || !(lr >= 0.f)) {
+    set_error("rc_mlp_fit_step: N must be positive and lr >= 0");
     return RC_ERR_ARG;
   }
-  return learn_train(c, gamma, dE, g_ref, n_min, lr, loss_h, grad);
+  double* d = nullptr;
+  if (hipMalloc((void**)&d, sizeof(double)) != hipSuccess) {
+    set_error("rc_mlp_fit_step: allocation failed");
+    return RC_ERR_NOMEM;
+  }
+  rc_status st = mlp_fit_step(m->m, X, R, N, lr, d, grad, m->m.stream);
+  if (st == RC_OK && hipMemcpyAsync(loss_h, d, sizeof(double), hipMemcpyDeviceToHost, m->m.stream) != hipSuccess) {
+    set_error("rc_mlp_fit_step: copy of the loss failed");
+    st = RC_ERR_HIP;
+  }
+  if (hipStreamSynchronize(m->m.stream) != hipSuccess && st == RC_OK) {
+    set_error("rc_mlp_fit_step: stream synchronisation failed");
+    st = RC_ERR_HIP;
+  }
+  hipFree(d);
+  return st;
 }

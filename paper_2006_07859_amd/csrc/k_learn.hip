@@ -1,4 +1,5 @@
-// Learned multilevel preconditioner: the MLP and the per-vertex features.
+// Learned smoother weights of the multigrid V-cycle: the MLP and the
+// per-vertex features, the training targets and the regression loss.
 //
 // MLP (3 layers, width 64): y = softplus(W3 . relu(W2^T relu(W1^T x + b1) + b2) + b3)
 // for every row x of 8 features.  Parameters are kept in FP32 (master copy,
@@ -13,12 +14,19 @@
 // weight gradients.  Flat parameter order: W1 [8][64], b1, W2 [64][64], b2,
 // W3 [64], b3.
 //
-// Features of vertex v on level l (a closed loop numbered along itself):
-// l / (levels - 1); log of the mean incident edge length over the level's
-// mean edge length; turning angle between the incoming and outgoing edge;
-// unit vertex tangent (3); log of diag(A_l)_v over its level mean; log of the
-// distance to the nearest vertex more than 4 steps away along the loop over
-// the mean incident edge length.
+// The network predicts p_v = 1 + y_v, a diagonal scaling of the level's
+// operator A_l: the target T_v = r_v lambda_l with r_v = sum_w |A_vw| / A_vv
+// (the row's l1 norm over its diagonal, >= 2 since A annihilates constants)
+// and lambda_l the largest eigenvalue of D_r^-1 A_l, D_r = diag(r_v A_vv)
+// (<= 1 by Gershgorin).  With D = diag(T_v A_vv) the spectrum of D^-1 A_l
+// tops out at exactly 1, so the smoother's Chebyshev interval is fixed at
+// [frac, 1] with no spectral estimate.
+//
+// Features of vertex v on a level of n vertices (a closed loop numbered
+// along itself): log2(n) / 16; log of the mean incident edge length over the
+// level's mean edge length; turning angle between the incoming and outgoing
+// edge; unit vertex tangent (3); log of diag(A_l)_v over its level mean; log
+// of the incoming over the outgoing edge length.
 
 #include <algorithm>
 #include <cmath>
@@ -247,6 +255,7 @@ __global__ void k_feat_local(const double* __restrict__ gam, const int2* __restr
   for (int c = 0; c < 3; ++c) o[1 + c] = t[c] / tn;
   o[4] = log(diag[v]);
   o[5] = lout;  // the outgoing edge's length: their mean is the level's mean edge length
+  o[6] = lin;
 }
 
 // sums[0] = mean edge length (each edge is one vertex's outgoing edge),
@@ -275,51 +284,107 @@ __global__ __launch_bounds__(256) void k_level_means(const double* __restrict__ 
   }
 }
 
-// Nearest vertex more than `sep` steps away along the loop (vertices numbered
-// along the loop); source vertices staged in LDS tiles.
-__global__ __launch_bounds__(256) void k_feat_far(const double* __restrict__ gam, int n, int sep,
-                                                  double* __restrict__ dmin) {
-  __shared__ double sx[256], sy[256], sz[256];
-  const int v = blockIdx.x * 256 + threadIdx.x;
-  const bool act = v < n;
-  const double px = act ? gam[3 * v] : 0, py = act ? gam[3 * v + 1] : 0, pz = act ? gam[3 * v + 2] : 0;
-  double best = INFINITY;
-  for (int t0 = 0; t0 < n; t0 += 256) {
-    __syncthreads();
-    if (t0 + threadIdx.x < n) {
-      sx[threadIdx.x] = gam[3 * (t0 + threadIdx.x)];
-      sy[threadIdx.x] = gam[3 * (t0 + threadIdx.x) + 1];
-      sz[threadIdx.x] = gam[3 * (t0 + threadIdx.x) + 2];
-    }
-    __syncthreads();
-    const int cnt = min(256, n - t0);
-    for (int u = 0; u < cnt; ++u) {
-      int d = abs(t0 + u - v);
-      d = min(d, n - d);
-      if (d <= sep) continue;
-      const double dx = sx[u] - px, dy = sy[u] - py, dz = sz[u] - pz;
-      best = fmin(best, dx * dx + dy * dy + dz * dz);
-    }
-  }
-  if (act) dmin[v] = sqrt(best);
-}
-
 // X rows of one level (float [n][8]) from the pieces above.
 __global__ void k_feat_rows(const double* __restrict__ loc, const double* __restrict__ lbar,
-                            const double* __restrict__ dmin, const double* __restrict__ sums, int n, double level,
-                            float* __restrict__ X) {
+                            const double* __restrict__ sums, int n, float* __restrict__ X) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const double* o = loc + 8 * (size_t)v;
   float* x = X + (size_t)v * kIn;
-  x[0] = (float)level;
+  x[0] = (float)(log2((double)n) / 16.0);
   x[1] = (float)log(lbar[v] / sums[0]);
   x[2] = (float)o[0];
   x[3] = (float)o[1];
   x[4] = (float)o[2];
   x[5] = (float)o[3];
   x[6] = (float)(o[4] - log(sums[1]));
-  x[7] = (float)log(dmin[v] / lbar[v]);
+  x[7] = (float)log(o[6] / o[5]);
+}
+
+// ---------------------------------------------------------------------------
+// training targets and loss
+// ---------------------------------------------------------------------------
+// r_v = sum_w |A_vw| / A_vv for the rows of a dense FP64 matrix and the
+// scaling sc_v = (r_v A_vv)^-1/2 (one wave per row, fixed-order lane sums
+// then a wave reduction).
+__global__ __launch_bounds__(256) void k_row_l1_ratio(const double* __restrict__ A, int n, double* __restrict__ r,
+                                                      double* __restrict__ sc) {
+  const int v = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (v >= n) return;
+  const double* row = A + (size_t)v * n;
+  double a = 0.0;
+  for (int w = lane; w < n; w += 64) a += fabs(row[w]);
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+  if (lane == 0) {
+    r[v] = a / row[v];
+    sc[v] = 1.0 / sqrt(a);
+  }
+}
+
+// y = S x with S = diag(sc) A diag(sc) for a dense symmetric A (one wave per row).
+__global__ __launch_bounds__(256) void k_sym_scaled_mv(const double* __restrict__ A, const double* __restrict__ sc,
+                                                       const double* __restrict__ x, int n, double* __restrict__ y) {
+  const int v = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (v >= n) return;
+  const double* row = A + (size_t)v * n;
+  double a = 0.0;
+  for (int w = lane; w < n; w += 64) a += row[w] * sc[w] * x[w];
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+  if (lane == 0) y[v] = sc[v] * a;
+}
+
+// x_v = (-1)^v: the alternating vector, close to the top eigenvector of the
+// scaled operator of a loop (its highest frequency)
+__global__ void k_alternating(int n, double* __restrict__ x) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) x[v] = (v & 1) ? -1.0 : 1.0;
+}
+
+// T_v = r_v lambda (float)
+__global__ void k_ratio_targets(const double* __restrict__ r, const double* __restrict__ lam, int n,
+                                float* __restrict__ T) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) T[v] = (float)(r[v] * lam[0]);
+}
+
+// Regression of p = 1 + y on the ratio r in log space, under-prediction
+// (p < r, where the Gershgorin bound of the smoother fails) weighted by
+// kFitUnder: per row loss w (log p - log r)^2, dY = d(mean loss)/dy; the
+// loss summed per workgroup into part.
+constexpr float kFitUnder = 4.f;
+__global__ __launch_bounds__(256) void k_fit_loss(const float* __restrict__ Y, const float* __restrict__ R, int N,
+                                                  float* __restrict__ dY, double* __restrict__ part) {
+  __shared__ double sm[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double l = 0.0;
+  if (i < N) {
+    const float p = 1.f + Y[i];
+    const float e = logf(p) - logf(R[i]);
+    const float w = p < R[i] ? kFitUnder : 1.f;
+    l = (double)(w * e * e);
+    dY[i] = 2.f * w * e / (p * (float)N);
+  }
+  sm[threadIdx.x] = l;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sm[threadIdx.x] += sm[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ void k_sum_parts(const double* __restrict__ part, int n, double scale, double* __restrict__ out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double a = 0.0;
+    for (int k = 0; k < n; ++k) a += part[k];
+    out[0] = a * scale;
+  }
+}
+
+// The smoother's diagonal D_v = margin (1 + y_v) diag_v (its weights are 1 / D_v).
+__global__ void k_learned_diag(const float* __restrict__ Y, int n, double margin, double* __restrict__ diag) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) diag[v] *= margin * (1.0 + (double)Y[v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -432,20 +497,72 @@ rc_status mlp_adam(Mlp& M, const float* grad, float lr, hipStream_t s) {
   return RC_OK;
 }
 
-// Features of one level into X (float [n][8]); scratch: 10 n + 2 doubles.
-rc_status launch_level_features(const Curve& cv, const double* gam, const double* diag, int level, int levels,
-                                double* scratch, float* X, hipStream_t s) {
+// Features of one level into X (float [n][8]); scratch: 9 n + 2 doubles.
+rc_status launch_level_features(const Curve& cv, const double* gam, const double* diag, double* scratch, float* X,
+                                hipStream_t s) {
   const int n = cv.nV;
   double* lbar = scratch;
-  double* dmin = scratch + n;
-  double* loc = scratch + 2 * (size_t)n;
-  double* sums = scratch + 10 * (size_t)n;
+  double* loc = scratch + (size_t)n;
+  double* sums = scratch + 9 * (size_t)n;
   hipLaunchKernelGGL(k_feat_local, dim3(cdiv(n, 256)), dim3(256), 0, s, gam, cv.edges, cv.inc_off, cv.inc, n, diag,
                      lbar, loc);
   hipLaunchKernelGGL(k_level_means, dim3(1), dim3(256), 0, s, (const double*)loc, diag, n, sums);
-  hipLaunchKernelGGL(k_feat_far, dim3(cdiv(n, 256)), dim3(256), 0, s, gam, n, kFeatSep, dmin);
   hipLaunchKernelGGL(k_feat_rows, dim3(cdiv(n, 256)), dim3(256), 0, s, (const double*)loc, (const double*)lbar,
-                     (const double*)dmin, (const double*)sums, n, levels > 1 ? (double)level / (levels - 1) : 0.0, X);
+                     (const double*)sums, n, X);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+rc_status launch_row_l1_ratio(const double* A, int n, double* r, double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_l1_ratio, dim3(cdiv(n, 4)), dim3(256), 0, s, A, n, r, sc);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+rc_status launch_sym_scaled_mv(const double* A, const double* sc, const double* x, int n, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_sym_scaled_mv, dim3(cdiv(n, 4)), dim3(256), 0, s, A, sc, x, n, y);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+rc_status launch_alternating(int n, double* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_alternating, dim3(cdiv(n, 256)), dim3(256), 0, s, n, x);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+rc_status launch_ratio_targets(const double* r, const double* lam, int n, float* T, hipStream_t s) {
+  hipLaunchKernelGGL(k_ratio_targets, dim3(cdiv(n, 256)), dim3(256), 0, s, r, lam, n, T);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+rc_status launch_learned_diag(const float* Y, int n, double margin, double* diag, hipStream_t s) {
+  hipLaunchKernelGGL(k_learned_diag, dim3(cdiv(n, 256)), dim3(256), 0, s, Y, n, margin, diag);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+// One regression step: forward (kept), loss and dY, backward, Adam (lr > 0).
+rc_status mlp_fit_step(Mlp& M, const float* X, const float* R, int N, float lr, double* loss_dev, float* grad_out,
+                       hipStream_t s) {
+  if (N <= 0) {
+    set_error("MLP fit: N must be positive");
+    return RC_ERR_ARG;
+  }
+  RC_TRY(M.ensure_rows(N));  // the row buffers (M.Y among them) exist before they are passed on
+  RC_TRY(mlp_forward(M, X, N, M.Y, true, s));
+  const int nb = cdiv(N, 256);
+  if (nb > M.cap) {
+    set_error("MLP fit: too many rows for the loss buffer");
+    return RC_ERR_ARG;
+  }
+  double* part = (double*)M.D1;  // [nb] doubles: the first-layer deltas are written after the loss
+  hipLaunchKernelGGL(k_fit_loss, dim3(nb), dim3(256), 0, s, (const float*)M.Y, R, N, M.dY, part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, (const double*)part, nb, 1.0 / N, loss_dev);
+  RC_TRY(mlp_backward(M, X, N, M.dY, M.grad, s));
+  if (grad_out) RC_HIP(hipMemcpyAsync(grad_out, M.grad, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, s));
+  if (lr > 0.f) RC_TRY(mlp_adam(M, M.grad, lr, s));
   RC_HIP(hipGetLastError());
   return RC_OK;
 }

@@ -334,7 +334,6 @@ rc_status launch_lowp_apply32(const LowpOp& op, const double* X, double* Y, hipS
 // Learned multilevel preconditioner (k_learn.hip): the MLP and the features.
 constexpr int kMlpIn = 8, kMlpWidth = 64;
 constexpr int kMlpParams = kMlpIn * kMlpWidth + kMlpWidth + kMlpWidth * kMlpWidth + kMlpWidth + kMlpWidth + 1;
-constexpr int kFeatSep = 4;  // vertices at most this far apart along the loop are not "other parts" of it
 struct Mlp {
   float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *opart = nullptr;
   _Float16* w16 = nullptr;
@@ -351,9 +350,21 @@ rc_status mlp_forward(Mlp& M, const float* X, int N, float* Y, bool keep, hipStr
 rc_status mlp_backward(Mlp& M, const float* X, int N, const float* dY, float* grad, hipStream_t s);
 rc_status mlp_adam(Mlp& M, const float* grad, float lr, hipStream_t s);
 // Features of one level (a loop numbered along itself) into X [n][8];
-// scratch holds 10 n + 2 doubles.
-rc_status launch_level_features(const Curve& cv, const double* gam, const double* diag, int level, int levels,
-                                double* scratch, float* X, hipStream_t s);
+// scratch holds 9 n + 2 doubles.
+rc_status launch_level_features(const Curve& cv, const double* gam, const double* diag, double* scratch, float* X,
+                                hipStream_t s);
+// r[v] = sum_w |A_vw| / A_vv and sc[v] = (sum_w |A_vw|)^-1/2 for a dense FP64
+// n x n matrix; y = diag(sc) A diag(sc) x; x = the alternating vector;
+// T = r lambda[0] (float).
+rc_status launch_row_l1_ratio(const double* A, int n, double* r, double* sc, hipStream_t s);
+rc_status launch_sym_scaled_mv(const double* A, const double* sc, const double* x, int n, double* y, hipStream_t s);
+rc_status launch_alternating(int n, double* x, hipStream_t s);
+rc_status launch_ratio_targets(const double* r, const double* lam, int n, float* T, hipStream_t s);
+// diag[v] *= margin (1 + Y[v]): the learned smoother diagonal.
+rc_status launch_learned_diag(const float* Y, int n, double margin, double* diag, hipStream_t s);
+// One regression step of the MLP on (X, R) (see k_learn.hip); loss_dev: device double.
+rc_status mlp_fit_step(Mlp& M, const float* X, const float* R, int N, float lr, double* loss_dev, float* grad_out,
+                       hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // dense and vector helpers (k_linalg.hip)

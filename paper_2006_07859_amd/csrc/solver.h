@@ -167,9 +167,10 @@ struct rc_ctx {
   rc_mlp* mlp = nullptr;          // attached, not owned
   int learn_nmin = -1, learn_N = 0, learn_cap = 0;
   std::vector<int> learn_off;     // row offset of every level
-  double *learn_diag = nullptr, *learn_scal = nullptr, *learn_u = nullptr, *learn_w = nullptr, *learn_tmp = nullptr;
+  double* learn_diag = nullptr;
   double* learn_scratch = nullptr;
-  float *learn_X = nullptr, *learn_Y = nullptr, *learn_dY = nullptr;
+  float *learn_X = nullptr, *learn_Y = nullptr;
+  bool mg_learned = false;  // the V-cycle's smoothers take the attached MLP's weights
 };
 
 struct rc_mlp {
@@ -210,10 +211,7 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
                       const rc_solve_opts& so, LsResult* out);
 
 rc_status learn_prepare_levels(rc_ctx* c, int n_min);
-rc_status learn_prepare(rc_ctx* c, const double* gamma, int n_min, bool use_mlp, bool keep);
-rc_status learn_apply(rc_ctx* c, const double* r, double* z);
-rc_status learn_train(rc_ctx* c, const double* gamma, const double* dE, const double* g_ref, int n_min, float lr,
-                      double* loss, float* grad_out);
+rc_status learn_levels_at(rc_ctx* c, const double* gamma, int n_min, bool features, float* R);
 void learn_free(rc_ctx* c);
 
 // batch.hip

@@ -756,6 +756,9 @@ static rc_status apply_level(rc_ctx* c, int l, const double* X, double* Y) {
   return apply_A(c, level_curve(c, l), X, Y, c->dtype);
 }
 
+// Learned smoother diagonals: the network's ratio prediction times this margin.
+constexpr double kLearnedMargin = 1.05;
+
 static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
   RC_TRY(mg_build(c));
   hipStream_t s = c->stream;
@@ -790,9 +793,7 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
   for (int l = 0; l < nl - 1; ++l) c->mg_weighted = c->mg_weighted && level_cons(c, l).nb <= kProjMaxBorder;
   for (int l = 0; l < nl - 1; ++l) {
     const Curve& cv = level_curve(c, l);
-    Cons& K = level_cons(c, l);
     MGLevelState& st = c->mg[l];
-    const int n = cv.nV;
     if (l < c->lowp_levels)
       RC_TRY(launch_assemble_lowp(cv, level_lowp(c, l), c->lowp_fmt, c->lowp_band, l == 0 && c->lowp_outer == 1,
                                   c->alpha, c->beta, st.diag, s));
@@ -800,12 +801,35 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
       RC_TRY(launch_bct_apply(cv, *cv.hbvh, *cv.hbct, c->alpha, c->beta, st.pw, st.t, s, st.diag));
     else
       RC_TRY(launch_sobolev(cv, c->alpha, c->beta, prec, st.pw, st.t, st.diag, s));
+    if (c->mg_learned)
+      RC_TRY(launch_level_features(cv, l == 0 ? gamma : c->levels[l]->gamma, st.diag, c->learn_scratch,
+                                   c->learn_X + (size_t)kMlpIn * c->learn_off[l], s));
+  }
+  if (c->mg_learned) {
+    // the smoothers' diagonals D_v = margin (1 + y_v) diag_v from the network's ratio predictions
+    const int rows = c->learn_off[nl - 1];
+    RC_TRY(mlp_forward(c->mlp->m, c->learn_X, rows, c->learn_Y, false, s));
+    for (int l = 0; l < nl - 1; ++l)
+      RC_TRY(launch_learned_diag(c->learn_Y + c->learn_off[l], level_curve(c, l).nV, kLearnedMargin, c->mg[l].diag,
+                                 s));
+  }
+  for (int l = 0; l < nl - 1; ++l) {
+    const Curve& cv = level_curve(c, l);
+    Cons& K = level_cons(c, l);
+    MGLevelState& st = c->mg[l];
+    const int n = cv.nV;
     if (c->mg_weighted) {  // factors of C W C^T, W = D^-1
       Cons& Kw = level_cons_w(c, l);
       if (Kw.mask != K.mask || !Kw.geo) RC_TRY(cons_alloc(c, cv, Kw, K.mask));
       RC_HIP(hipMemcpyAsync(Kw.x0, K.x0, sizeof(double) * 3, hipMemcpyDeviceToDevice, s));
       hipLaunchKernelGGL(k_recip, dim3(cdiv(n, 256)), dim3(256), 0, s, st.diag, n, st.w);
       RC_TRY(cons_prepare(c, cv, Kw, l == 0 ? gamma : c->levels[l]->gamma, st.w));
+    }
+    if (c->mg_learned) {
+      // the learned diagonal places the top of the spectrum of D^-1 A at 1 / margin, and the
+      // projected operators' spectra lie inside that of D^-1 A
+      st.lmax = 1.0;
+      continue;
     }
     // lambda_max of the smoother's preconditioned operator (P D^-1 P A P, or M A with the
     // weighted projector M) by power iteration, warm-started from the last call's vector: at
@@ -966,11 +990,8 @@ static rc_status vcycle(rc_ctx* c, int l, const double* b, double* x) {
 // ---------------------------------------------------------------------------
 // projected PCG:  P Abar P y = P b, y in range(P)   (App. B.3.3)
 // ---------------------------------------------------------------------------
-rc_status learn_apply(rc_ctx* c, const double* r, double* z);
-
 static rc_status precondition(rc_ctx* c, int kind, const double* r, double* z) {
-  if (kind == RC_SOLVE_PCG_MULTILEVEL || kind == RC_SOLVE_PCG_LEARNED) return learn_apply(c, r, z);
-  if (kind == RC_SOLVE_PCG_MG) {
+  if (kind == RC_SOLVE_PCG_MG || kind == RC_SOLVE_PCG_LEARNED) {
     MGLevelState& st = c->mg[0];
     return vcycle(c, 0, r, z);  // the V-cycle only reads its right-hand side
   }
@@ -1026,7 +1047,7 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
   int it = 0;
   double res = 1.0, res_sweep = 1.0;  // residual at the start of the current sweep
   bool converged = false;
-  const bool watch = o.fallback_after > 0 && (o.solver == RC_SOLVE_PCG_MULTILEVEL || o.solver == RC_SOLVE_PCG_LEARNED);
+  const bool watch = o.fallback_after > 0 && o.solver == RC_SOLVE_PCG_LEARNED;
   int growing = 0;  // consecutive iterations with a growing recurrence residual
   // with an inexact Krylov operator (FP32 block or FP32 pairs) a sweep ends
   // early when its recurrence residual stalls at the operator's floor (less
@@ -1111,7 +1132,7 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
 // entry points used by the C ABI
 // ---------------------------------------------------------------------------
 rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o) {
-  if (o.solver < RC_SOLVE_DENSE || o.solver > RC_SOLVE_PCG_LEARNED) {
+  if (o.solver < RC_SOLVE_DENSE || o.solver > RC_SOLVE_PCG_LEARNED || o.solver == 3) {
     set_error("solve options: unknown solver kind");
     return RC_ERR_ARG;
   }
@@ -1124,7 +1145,8 @@ rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o)
     return RC_ERR_ARG;
   }
   c->lowp_levels = 0;
-  if (o.bct_theta < 0.0 || (o.bct_theta > 0.0 && (o.lowp || o.solver != RC_SOLVE_PCG_MG))) {
+  if (o.bct_theta < 0.0 ||
+      (o.bct_theta > 0.0 && (o.lowp || (o.solver != RC_SOLVE_PCG_MG && o.solver != RC_SOLVE_PCG_LEARNED)))) {
     set_error("solve options: the block-cluster-tree operator (bct_theta > 0) serves the multigrid solver "
               "without the precision path");
     return RC_ERR_ARG;
@@ -1144,15 +1166,16 @@ rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o)
   c->lowp_fmt = o.lowp;
   c->lowp_band = o.lowp_band;
   c->lowp_outer = o.lowp_outer;
-  if (o.solver == RC_SOLVE_PCG_MULTILEVEL || o.solver == RC_SOLVE_PCG_LEARNED) {
-    if (o.lowp) {
-      set_error("solve options: the 16-bit operator serves the Jacobi and multigrid preconditioners only");
+  c->mg_learned = false;
+  if (o.solver == RC_SOLVE_PCG_LEARNED) {
+    if (!c->mlp) {
+      set_error("learned smoother: no MLP attached (rc_learned_attach)");
       return RC_ERR_ARG;
     }
-    RC_TRY(learn_prepare(c, gamma, o.mg_min_vertices, o.solver == RC_SOLVE_PCG_LEARNED, false));
-    return load_geometry(c, gamma);
+    RC_TRY(learn_prepare_levels(c, o.mg_min_vertices));
+    c->mg_learned = true;
   }
-  if (o.solver == RC_SOLVE_PCG_MG) {
+  if (o.solver == RC_SOLVE_PCG_MG || o.solver == RC_SOLVE_PCG_LEARNED) {
     if (c->mg_min != o.mg_min_vertices) {
       mg_free(c);
       c->mg_min = o.mg_min_vertices;
@@ -1193,8 +1216,7 @@ rc_status solve_gradient(rc_ctx* c, const double* gamma, const double* rhs, doub
   *fell = 0;
   RC_TRY(prepare_solver(c, gamma, o));
   rc_status st = solve_prepared(c, rhs, out, o, iters, res);
-  if (st == RC_ERR_NOT_CONVERGED && o.fallback_after > 0 &&
-      (o.solver == RC_SOLVE_PCG_MULTILEVEL || o.solver == RC_SOLVE_PCG_LEARNED)) {
+  if (st == RC_ERR_NOT_CONVERGED && o.fallback_after > 0 && o.solver == RC_SOLVE_PCG_LEARNED) {
     if (trace_on()) fprintf(stderr, "[rc pcg] falling back to multigrid after %d iterations\n", *iters);
     const int spent = *iters;
     o.solver = RC_SOLVE_PCG_MG;
@@ -1344,48 +1366,16 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
 }
 
 // ---------------------------------------------------------------------------
-// Multilevel preconditioner M^-1 = sum_l P_l D_l P_l^T over the multigrid
-// hierarchy (P_0 = Id, P_l = J_1 ... J_l), applied as P M^-1 P, with
-// D_l = diag(y_l / diag(A_l)): y = 1 (hand-weighted) or the attached MLP's
-// output on the level features (learned).  Vectors of all levels are stacked
-// finest first, level l at row learn_off[l].
+// Learned smoother weights (k_learn.hip): the hierarchy of the multigrid
+// V-cycle, one closed loop numbered along itself on every level; features and
+// FP64 diagonals of every level stacked finest first (level l at row
+// learn_off[l]), the network's output, and the regression targets.
 // ---------------------------------------------------------------------------
-// scal = y / diag (y = null: 1 / diag)
-__global__ void k_learn_scal(const float* __restrict__ y, const double* __restrict__ diag, int N,
-                             double* __restrict__ scal) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) scal[i] = (y ? (double)y[i] : 1.0) / diag[i];
-}
-
-// z_l = scal_l u_l + J_{l+1} z_{l+1} (zc = null on the coarsest level)
-__global__ void k_learn_down(const int2* __restrict__ pr, int n, const double* __restrict__ zc,
-                             const double* __restrict__ scal, const double* __restrict__ u, double* __restrict__ z) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const double d = scal[v];
-  int2 ab = pr ? pr[v] : make_int2(0, 0);
-  for (int k = 0; k < 3; ++k)
-    z[3 * v + k] = d * u[3 * v + k] + (zc ? 0.5 * (zc[3 * ab.x + k] + zc[3 * ab.y + k]) : 0.0);
-}
-
-// dY_i = sum_c w_i,c u_i,c / diag_i: the loss gradient with respect to y
-__global__ void k_learn_dy(const double* __restrict__ w, const double* __restrict__ u, const double* __restrict__ diag,
-                           int N, float* __restrict__ dY) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  dY[i] = (float)((w[3 * i] * u[3 * i] + w[3 * i + 1] * u[3 * i + 1] + w[3 * i + 2] * u[3 * i + 2]) / diag[i]);
-}
-
 void learn_free(rc_ctx* c) {
   dfree(c->learn_diag);
-  dfree(c->learn_scal);
-  dfree(c->learn_u);
-  dfree(c->learn_w);
-  dfree(c->learn_tmp);
   dfree(c->learn_scratch);
   dfree(c->learn_X);
   dfree(c->learn_Y);
-  dfree(c->learn_dY);
   c->learn_cap = 0;
   c->learn_nmin = -1;
 }
@@ -1394,7 +1384,7 @@ void learn_free(rc_ctx* c) {
 // whose vertices are numbered along it (checked once per hierarchy).
 rc_status learn_prepare_levels(rc_ctx* c, int n_min) {
   if (n_min < 4) {
-    set_error("multilevel preconditioner: n_min must be at least 4");
+    set_error("learned smoother: n_min must be at least 4");
     return RC_ERR_ARG;
   }
   if (c->mg_min != n_min) {
@@ -1408,7 +1398,7 @@ rc_status learn_prepare_levels(rc_ctx* c, int n_min) {
   for (int i = 0; ok && i < n0; ++i)
     ok = c->curve.h_edges[2 * i] == i && c->curve.h_edges[2 * i + 1] == (i + 1) % n0;
   if (!ok) {
-    set_error("multilevel preconditioner: needs one closed loop with edges (i, i + 1 mod n)");
+    set_error("learned smoother: needs one closed loop with edges (i, i + 1 mod n)");
     return RC_ERR_UNSUPPORTED;
   }
   RC_TRY(mg_build(c));
@@ -1418,7 +1408,7 @@ rc_status learn_prepare_levels(rc_ctx* c, int n_min) {
     bool good = chs.size() == 1 && chs[0].loop;
     for (int i = 0; good && i < (int)chs[0].verts.size(); ++i) good = chs[0].verts[i] == i;
     if (!good) {
-      set_error("multilevel preconditioner: a level is not one loop numbered along itself");
+      set_error("learned smoother: a level is not one loop numbered along itself");
       return RC_ERR_UNSUPPORTED;
     }
   }
@@ -1429,14 +1419,9 @@ rc_status learn_prepare_levels(rc_ctx* c, int n_min) {
     RC_TRY(sync(c));
     learn_free(c);
     RC_TRY(dalloc(&c->learn_diag, N));
-    RC_TRY(dalloc(&c->learn_scal, N));
-    RC_TRY(dalloc(&c->learn_u, 3 * (size_t)N));
-    RC_TRY(dalloc(&c->learn_w, 3 * (size_t)N));
-    RC_TRY(dalloc(&c->learn_tmp, 3 * (size_t)N));
-    RC_TRY(dalloc(&c->learn_scratch, 10 * (size_t)n0 + 2));
+    RC_TRY(dalloc(&c->learn_scratch, 9 * (size_t)n0 + 2));
     RC_TRY(dalloc(&c->learn_X, (size_t)kMlpIn * N));
     RC_TRY(dalloc(&c->learn_Y, N));
-    RC_TRY(dalloc(&c->learn_dY, N));
     c->learn_cap = N;
   }
   c->learn_N = N;
@@ -1444,14 +1429,16 @@ rc_status learn_prepare_levels(rc_ctx* c, int n_min) {
   return RC_OK;
 }
 
-// Level curves, FP64 diagonals, features and (y from the MLP or 1) the
-// scalings at gamma; keep stores the MLP activations for a backward pass.
-rc_status learn_prepare(rc_ctx* c, const double* gamma, int n_min, bool use_mlp, bool keep) {
+// Level curves at gamma (geometry loaded, finest last), and with X the
+// features and FP64 diagonals of every level; with R (device float[N]) the
+// targets T_v = r_v lambda_l from each level's dense FP64 operator A_l:
+// r_v = sum_w |A_vw| / A_vv, lambda_l the largest eigenvalue of
+// S = D_r^-1/2 A_l D_r^-1/2 (D_r = diag(r_v A_vv)) by kTargetPowerIts power
+// steps from the alternating vector (close to the top eigenvector), their
+// Rayleigh quotients a lower bound.
+constexpr int kTargetPowerIts = 60;
+rc_status learn_levels_at(rc_ctx* c, const double* gamma, int n_min, bool features, float* R) {
   RC_TRY(learn_prepare_levels(c, n_min));
-  if (use_mlp && !c->mlp) {
-    set_error("learned preconditioner: no MLP attached (rc_learned_attach)");
-    return RC_ERR_ARG;
-  }
   hipStream_t s = c->stream;
   const int nl = (int)c->levels.size();
   const double* g = gamma;
@@ -1461,95 +1448,65 @@ rc_status learn_prepare(rc_ctx* c, const double* gamma, int n_min, bool use_mlp,
                        L.gamma);
     g = L.gamma;
   }
-  RC_HIP(hipMemsetAsync(c->learn_tmp, 0, sizeof(double) * 3 * c->nV, s));
-  for (int l = nl - 1; l >= 0; --l) {  // finest last: its geometry stays loaded
+  double* dense = nullptr;
+  if (R) {
+    const size_t n0 = (size_t)c->curve.nV;
+    if (n0 > 16384) {
+      set_error("learned smoother targets: at most 16,384 vertices (dense FP64 level operators)");
+      return RC_ERR_ARG;
+    }
+    RC_TRY(dalloc(&dense, n0 * n0 + 4 * n0));
+  }
+  rc_status st = RC_OK;
+  for (int l = nl - 1; l >= 0 && st == RC_OK; --l) {  // finest last: its geometry stays loaded
     const Curve& cv = level_curve(c, l);
     const double* gl = l == 0 ? gamma : c->levels[l]->gamma;
     const int o = c->learn_off[l];
-    RC_TRY(launch_geometry(cv, gl, RC_F32, s));
-    RC_TRY(launch_sobolev(cv, c->alpha, c->beta, RC_F64, c->learn_tmp, nullptr, c->learn_diag + o, s));
-    RC_TRY(launch_level_features(cv, gl, c->learn_diag + o, l, nl, c->learn_scratch, c->learn_X + (size_t)kMlpIn * o,
-                                 s));
+    st = launch_geometry(cv, gl, RC_F32, s);
+    if (st == RC_OK && features) {
+      hipMemsetAsync(c->learn_scratch, 0, sizeof(double) * 3 * cv.nV, s);  // a zero operand: only the diagonal
+      st = launch_sobolev(cv, c->alpha, c->beta, RC_F64, c->learn_scratch, nullptr, c->learn_diag + o, s);
+      if (st == RC_OK)
+        st = launch_level_features(cv, gl, c->learn_diag + o, c->learn_scratch, c->learn_X + (size_t)kMlpIn * o, s);
+    }
+    if (st == RC_OK && R) {
+      const int n = cv.nV;
+      double* r = dense + (size_t)n * n;
+      double* sc = r + n;
+      double* x = sc + n;
+      double* y = x + n;
+      st = launch_assemble_dense(cv, c->alpha, c->beta, dense, s);
+      if (st == RC_OK) st = launch_row_l1_ratio(dense, n, r, sc, s);
+      if (st == RC_OK) st = launch_alternating(n, x, s);
+      double lam = 0.0;
+      for (int it = 0; st == RC_OK && it < kTargetPowerIts; ++it) {
+        vec_dot(x, x, n, c->red, c->scal, s);
+        st = launch_sym_scaled_mv(dense, sc, x, n, y, s);
+        if (st != RC_OK) break;
+        vec_dot(x, y, n, c->red, c->scal + 1, s);
+        double h[2];
+        st = fetch(c, c->scal, h, 2);
+        if (st != RC_OK) break;
+        lam = h[1] / h[0];  // Rayleigh quotient of x
+        double h2;
+        vec_dot(y, y, n, c->red, c->scal + 2, s);
+        st = fetch(c, c->scal + 2, &h2, 1);
+        if (st != RC_OK) break;
+        vec_axpby(1.0 / std::sqrt(h2), y, 0.0, x, n, s);
+      }
+      if (st == RC_OK) {
+        RC_HIP(hipMemcpyAsync(c->scal + 3, &lam, sizeof(double), hipMemcpyHostToDevice, s));
+        st = launch_ratio_targets(r, c->scal + 3, n, R + o, s);
+        if (st == RC_OK) st = sync(c);
+      }
+    }
   }
-  const int N = c->learn_N;
-  if (use_mlp) RC_TRY(mlp_forward(c->mlp->m, c->learn_X, N, c->learn_Y, keep, s));
-  hipLaunchKernelGGL(k_learn_scal, dim3(cdiv(N, 256)), dim3(256), 0, s, use_mlp ? (const float*)c->learn_Y : nullptr,
-                     (const double*)c->learn_diag, N, c->learn_scal);
-  RC_HIP(hipGetLastError());
-  return RC_OK;
-}
-
-// u_0 = P r and u_l = J_l^T u_{l-1} into learn_u (or, for the backward pass, w).
-static void learn_restrict_all(rc_ctx* c, const double* r, double* u) {
-  hipStream_t s = c->stream;
-  cons_project(c, c->curve, c->cons, r, u);
-  for (int l = 1; l < (int)c->levels.size(); ++l) {
-    const Level& L = *c->levels[l];
-    hipLaunchKernelGGL(k_restrict, dim3(cdiv(L.curve.nV, 256)), dim3(256), 0, s, L.restr_off, L.restr_idx, L.prolong,
-                       L.curve.nV, u + 3 * (size_t)c->learn_off[l - 1], u + 3 * (size_t)c->learn_off[l]);
+  if (dense) {
+    const rc_status s2 = sync(c);
+    dfree(dense);
+    if (st == RC_OK) st = s2;
   }
-}
-
-// z = P M^-1 P r with the scalings of the last learn_prepare.
-rc_status learn_apply(rc_ctx* c, const double* r, double* z) {
-  hipStream_t s = c->stream;
-  learn_restrict_all(c, r, c->learn_u);
-  const int nl = (int)c->levels.size();
-  for (int l = nl - 1; l >= 0; --l) {
-    const int n = level_curve(c, l).nV, o = c->learn_off[l];
-    const bool coarsest = l == nl - 1;
-    hipLaunchKernelGGL(k_learn_down, dim3(cdiv(n, 256)), dim3(256), 0, s,
-                       coarsest ? (const int2*)nullptr : (const int2*)c->levels[l + 1]->prolong, n,
-                       coarsest ? (const double*)nullptr : (const double*)(c->learn_tmp + 3 * (size_t)c->learn_off[l + 1]),
-                       (const double*)(c->learn_scal + o), (const double*)(c->learn_u + 3 * (size_t)o),
-                       c->learn_tmp + 3 * (size_t)o);
-  }
-  cons_project(c, c->curve, c->cons, c->learn_tmp, z);
-  RC_HIP(hipGetLastError());
-  return RC_OK;
-}
-
-// One training sample (see rc_learned_train_step): with z = P M^-1 P dE,
-// a = <z, g>_A, b = |z|_A^2, q = |g|_A^2, loss = 1 - a^2 / (b q) and
-// d loss / dz = w = P (2 a / (b q)) ((a / b) A z - A g); the derivative with
-// respect to the scaling of vertex v on level l is sum_c (P_l^T w)_v,c (P_l^T P dE)_v,c.
-rc_status learn_train(rc_ctx* c, const double* gamma, const double* dE, const double* g_ref, int n_min, float lr,
-                      double* loss, float* grad_out) {
-  if (!c->mlp) {
-    set_error("learned preconditioner: no MLP attached (rc_learned_attach)");
-    return RC_ERR_ARG;
-  }
-  hipStream_t s = c->stream;
-  const int n3 = 3 * c->nV;
-  RC_TRY(cons_prepare(c, c->curve, c->cons, gamma));
-  RC_TRY(learn_prepare(c, gamma, n_min, true, true));
-  RC_TRY(learn_apply(c, dE, c->z));
-  RC_TRY(launch_sobolev(c->curve, c->alpha, c->beta, RC_F32, c->z, c->q, nullptr, s));       // A z
-  RC_TRY(launch_sobolev(c->curve, c->alpha, c->beta, RC_F32, g_ref, c->tmp, nullptr, s));    // A g
-  double abq[3];
-  vec_dot(c->z, c->tmp, n3, c->red, c->scal, s);
-  vec_dot(c->z, c->q, n3, c->red, c->scal + 1, s);
-  vec_dot(g_ref, c->tmp, n3, c->red, c->scal + 2, s);
-  RC_TRY(fetch(c, c->scal, abq, 3));
-  const double a = abq[0], b = abq[1], q = abq[2];
-  if (!(b > 0) || !(q > 0)) {
-    set_error("learned preconditioner training: zero A-norm (z or g_ref)");
-    return RC_ERR_SINGULAR;
-  }
-  *loss = 1.0 - a * a / (b * q);
-  vec_copy(c->q, c->r, n3, s);
-  vec_axpby(-2.0 * a / (b * q), c->tmp, 2.0 * a * a / (b * b * q), c->r, n3, s);
-  learn_restrict_all(c, c->r, c->learn_w);
-  const int N = c->learn_N;
-  hipLaunchKernelGGL(k_learn_dy, dim3(cdiv(N, 256)), dim3(256), 0, s, (const double*)c->learn_w,
-                     (const double*)c->learn_u, (const double*)c->learn_diag, N, c->learn_dY);
-  Mlp& M = c->mlp->m;
-  RC_TRY(mlp_backward(M, c->learn_X, N, c->learn_dY, M.grad, s));
-  if (grad_out)
-    RC_HIP(hipMemcpyAsync(grad_out, M.grad, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, s));
-  if (lr > 0.f) RC_TRY(mlp_adam(M, M.grad, lr, s));
-  RC_HIP(hipGetLastError());
-  return sync(c);
+  return st;
 }
 
 }  // namespace rc
