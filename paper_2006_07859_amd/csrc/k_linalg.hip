@@ -791,7 +791,9 @@ void cons_sub_Zy(const double* Z, const double* yb, int nb, int np, double* yp, 
 //      the border rows' dot products wb = rows . x and of Z^T wp;
 //   2. k_proj_solve (one workgroup): the partial sums, yb, and the reduced
 //      boundary values U = M^-1 (g at the block boundaries);
-//   3. k_apply_CT_z: out = x - C^T y with yp = g - V U - W U - Z yb per row.
+//   3. k_apply_CT_z: out = x - C^T y with yp = g - V U - W U - Z yb per row;
+// steps 2 and 3 share one launch (k_solve_apply_CT_z, each workgroup
+// repeating step 2) when the reduced system has at most 128 rows.
 // With vertex degree <= 2 (curves), the row data (T_I and the edge's ends)
 // and each vertex's incident path rows with their signed tangents s(v) T_I
 // are packed per level (ProjRow, ProjVert), so that a row or vertex needs one
@@ -958,19 +960,22 @@ __device__ __forceinline__ void proj_prep_operand(const ProjData& d, int v, bool
 
 // out_v = in_v - [ sum_{path rows k at v} s(v) T_I (yp_k - (Z yb)_k) + sum_r yb[r] rows[r][v] ]
 // for vertex v (the body of k_apply_CT_z); val receives out_v (xacc_v when prep_x).
+// yb, U: the border solution and the reduced boundary values (global memory,
+// or LDS in the fused launch).
 __device__ __forceinline__ void apply_CT_z_vertex(const ProjData& d, int v, const double* __restrict__ in,
-                                                  double* __restrict__ out, double (&val)[3]) {
+                                                  double* __restrict__ out, double (&val)[3], const double* yb,
+                                                  const double* U) {
   const int np = d.np, nb = d.nb;
   const TriBlocks& L = d.tri;
   double ybr[kProjMaxBorder];
 #pragma unroll
-  for (int r = 0; r < kProjMaxBorder; ++r) ybr[r] = r < nb ? d.yb[r] : 0.0;
+  for (int r = 0; r < kProjMaxBorder; ++r) ybr[r] = r < nb ? yb[r] : 0.0;
   double acc[3] = {0, 0, 0};
   auto add_row = [&](int pr, double c0, double c1, double c2) {
     double y = d.g[pr];
     const int q = pr / L.S;
-    if (q < L.B - 1) y -= d.V[pr] * d.U[2 * q + 1];
-    if (q > 0) y -= d.W[pr] * d.U[2 * (q - 1)];
+    if (q < L.B - 1) y -= d.V[pr] * U[2 * q + 1];
+    if (q > 0) y -= d.W[pr] * U[2 * (q - 1)];
 #pragma unroll
     for (int r = 0; r < kProjMaxBorder; ++r)
       if (r < nb) y -= d.Z[(size_t)r * np + pr] * ybr[r];
@@ -1016,7 +1021,66 @@ __global__ __launch_bounds__(256) void k_apply_CT_z(const ProjData d, const doub
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const bool vert = v < d.nV;
   double val[3] = {0.0, 0.0, 0.0};
-  if (vert) apply_CT_z_vertex(d, v, in, out, val);
+  if (vert) apply_CT_z_vertex(d, v, in, out, val, d.yb, d.U);
+  if (d.pp) proj_prep_operand<256>(d, v, vert, val);
+}
+
+// k_proj_solve and k_apply_CT_z in one launch when the reduced system is
+// small (nr <= kFuseMaxNr): every workgroup sums the partials, solves the
+// border (yb) and applies M^-1 to the block-boundary values (U) itself, in
+// the order k_proj_solve uses, into LDS, then applies C^T y to its vertices.
+constexpr int kFuseMaxNr = 128;
+__global__ __launch_bounds__(256) void k_solve_apply_CT_z(const ProjData d, int nblk, const double* __restrict__ in,
+                                                          double* __restrict__ out) {
+  __shared__ double tot[kProjSlots], ybs[kProjMaxBorder];
+  __shared__ double rhs[kFuseMaxNr], Us[kFuseMaxNr], half_sum[256];
+  const int t = threadIdx.x, nb = d.nb;
+  const TriBlocks& L = d.tri;
+  const int nr = L.nr;
+  {  // slot q = t / 16 summed over the workgroups of k_proj_rows by 16 lanes
+    const int q = t / 16, sgm = t % 16;
+    double v = 0.0;
+    if ((q % kProjMaxBorder) < nb)
+      for (int k = sgm; k < nblk; k += 16) v += d.part[(size_t)k * kProjSlots + q];
+    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (sgm == 0) tot[q] = v;
+  }
+  for (int i = t; i < nr; i += 256) {
+    const int q = i / 2;
+    rhs[i] = d.g[(i % 2 == 0) ? (q + 1) * L.S - 1 : (q + 1) * L.S];
+  }
+  __syncthreads();
+  if (t < nb) {  // yb = S^-1 (wb - Z^T wp)
+    double v = 0.0;
+    for (int j = 0; j < nb; ++j) v += d.Sinv[t * nb + j] * (tot[j] - tot[kProjMaxBorder + j]);
+    ybs[t] = v;
+  }
+  {  // U = M^-1 rhs: row i by two threads (halves of j), four independent partial sums each
+    constexpr int kHalf = 128;
+    const int i = t % kHalf, h = t / kHalf;
+    const int jh = (nr + 1) / 2;
+    const int j0 = h * jh, j1 = min(nr, j0 + jh);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (i < nr) {
+      const double* col = d.Rt + i;
+      int j = j0;
+      for (; j + 4 <= j1; j += 4) {
+        s0 += col[(size_t)j * nr] * rhs[j];
+        s1 += col[(size_t)(j + 1) * nr] * rhs[j + 1];
+        s2 += col[(size_t)(j + 2) * nr] * rhs[j + 2];
+        s3 += col[(size_t)(j + 3) * nr] * rhs[j + 3];
+      }
+      for (; j < j1; ++j) s0 += col[(size_t)j * nr] * rhs[j];
+    }
+    half_sum[t] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (h == 0 && i < nr) Us[i] = half_sum[t] + half_sum[t + kHalf];
+  }
+  __syncthreads();
+  const int v = blockIdx.x * blockDim.x + t;
+  const bool vert = v < d.nV;
+  double val[3] = {0.0, 0.0, 0.0};
+  if (vert) apply_CT_z_vertex(d, v, in, out, val, ybs, Us);
   if (d.pp) proj_prep_operand<256>(d, v, vert, val);
 }
 
@@ -1169,6 +1233,10 @@ void cons_project_fused(const ProjData& d, const double* in, double* out, hipStr
   // one workgroup per block of path rows; at least enough for the vertices' border sums
   const int nblk = std::max(d.np > 0 ? d.tri.B : 1, std::min(64, cdiv(d.nV, kSpThreads)));
   hipLaunchKernelGGL(k_proj_rows, dim3(nblk), dim3(kSpThreads), 0, s, d, in);
+  if (d.tri.nr <= kFuseMaxNr) {
+    hipLaunchKernelGGL(k_solve_apply_CT_z, dim3(cdiv(d.nV, 256)), dim3(256), 0, s, d, nblk, in, out);
+    return;
+  }
   hipLaunchKernelGGL(k_proj_solve, dim3(1), dim3(kSpThreads), 0, s, d, nblk);
   hipLaunchKernelGGL(k_apply_CT_z, dim3(cdiv(d.nV, 256)), dim3(256), 0, s, d, in, out);
 }
