@@ -167,6 +167,11 @@ typedef struct {
   int32_t ccd;           /* 1 = start the search at 2/3 of the first collision time tau_max of the curve
                             moved along -g/|g| (Sec. 4.4; rc_first_collision_time), sought up to
                             1.5 tau0, so tau0 without a collision; 0 = start at tau0 */
+  double bh_theta;       /* > 0 (and < 0.5): rc_step's energy and differential and the search's trial
+                            energies are the Barnes-Hut approximations of rc_bh_differential (App. B.1,
+                            the edge-midpoint discretisation, leaf size 32) with this parameter, for
+                            large curves; the energy0 given to rc_line_search_step must then be one
+                            too.  0 = the exact all-pairs sums */
 } rc_ls_opts;
 
 typedef struct {

@@ -70,7 +70,7 @@ class BatchOpts(C.Structure):
 class LsOpts(C.Structure):
     _fields_ = [("c_armijo", C.c_double), ("shrink", C.c_double), ("tau0", C.c_double),
                 ("max_backtracks", C.c_int32), ("max_proj_iter", C.c_int32), ("proj_tol", C.c_double),
-                ("proj_solve_tol", C.c_double), ("ccd", C.c_int32)]
+                ("proj_solve_tol", C.c_double), ("ccd", C.c_int32), ("bh_theta", C.c_double)]
 
 
 class Stats(C.Structure):

@@ -117,6 +117,7 @@ void rc_default_ls_opts(rc_ls_opts* o) {
   o->proj_tol = 1e-10;
   o->proj_solve_tol = 1e-3;
   o->ccd = 0;
+  o->bh_theta = 0.0;
 }
 
 const char* rc_last_error(void) { return rc::last_error(); }
@@ -464,6 +465,10 @@ rc_status rc_step(rc_ctx* c, double* gamma, const rc_solve_opts* so, const rc_ls
   RC_TRY(check_ptrs({gamma}));
   rc_solve_opts o = resolve(so);
   rc_ls_opts l = resolve_ls(ls);
+  if (!(l.bh_theta >= 0.0 && l.bh_theta < 0.5)) {
+    set_error("rc_step: bh_theta must be 0 or lie in (0, 0.5)");
+    return RC_ERR_ARG;
+  }
   hipStream_t s = c->stream;
   // dE and g live in buffers that no solver routine touches
   double* dEb = c->dEs;
@@ -475,9 +480,15 @@ rc_status rc_step(rc_ctx* c, double* gamma, const rc_solve_opts* so, const rc_ls
   int nev = 0;
   RC_HIP(hipEventRecord(ev[nev++], s));
   do {
-    st = launch_geometry(c->curve, gamma, c->dtype, s);
-    if (st) break;
-    st = launch_tpe(c->curve, c->alpha, c->beta, c->dtype, true, c->scal + 8, dEb, s);
+    if (l.bh_theta > 0.0) {
+      st = launch_geometry(c->curve, gamma, RC_F32, s);
+      if (st) break;
+      st = launch_bh(c->curve, c->bvh, c->alpha, c->beta, l.bh_theta, kStepBhLeaf, c->scal + 8, dEb, s);
+    } else {
+      st = launch_geometry(c->curve, gamma, c->dtype, s);
+      if (st) break;
+      st = launch_tpe(c->curve, c->alpha, c->beta, c->dtype, true, c->scal + 8, dEb, s);
+    }
     if (st) break;
     RC_HIP(hipEventRecord(ev[nev++], s));
     st = fetch(c, c->scal + 8, &local.energy, 1);

@@ -22,6 +22,7 @@
 //   sum the exact edge-midpoint pairs, omitting edges that share a vertex.
 
 #include <algorithm>
+#include <vector>
 
 #include "pair_math.h"
 #include "rc_internal.h"
@@ -33,6 +34,9 @@ static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 constexpr int kBvhThreads = 256;
 constexpr int kBins = 64;
 constexpr int kStack = 64;
+// top-level split over many workgroups: levels of at most kBigMaxNodes nodes
+// whose mean size is at least kBigNode, in chunks of kBigChunk positions
+constexpr int kBigMaxNodes = 64, kBigNode = 8192, kBigChunk = 4096, kBigWords = 640;
 
 // tangent-points, SoA [6][nE]: T (3) then midpoint x (3)
 __global__ void k_tangent_points(const V4<float>* __restrict__ GA, const V4<float>* __restrict__ GB,
@@ -229,6 +233,281 @@ __global__ __launch_bounds__(kBvhThreads) void k_bvh_split(const float* __restri
     split[bid] = 1;
     node[lb + bid] = make_int4(s, n, 0, nl);
   }
+}
+
+// ---------------------------------------------------------------------------
+// The same split for the top levels (few nodes, many edges each) over many
+// workgroups: a node's range is cut into chunks of kBigChunk positions, and
+// every quantity the single-workgroup split takes (the six-axis box, the
+// per-axis histograms, the two child boxes of each candidate cut) is a
+// minimum, maximum or integer count, accumulated by chunk with atomics, so
+// the split (cut, axis, stable partition) is exactly that of k_bvh_split.
+// Floats take part in integer min / max through an order-preserving map.
+// Per node (kBigWords ints): box [6][2], hist [6][kBins], cand [6][2][6][2],
+// cut [6], nleft [6], plan (axis, left count, lo bits, inv_w bits).
+// ---------------------------------------------------------------------------
+constexpr int oBox = 0, oHist = oBox + 12, oCand = oHist + 6 * kBins, oCut = oCand + 144, oNl = oCut + 6,
+              oPlan = oNl + 6;
+static_assert(oPlan + 4 <= kBigWords, "per-node words of the top-level split");
+
+__device__ __forceinline__ int fkey(float f) {
+  const int i = __float_as_int(f);
+  return i >= 0 ? i : i ^ 0x7FFFFFFF;
+}
+__device__ __forceinline__ float fval(int k) { return __int_as_float(k >= 0 ? k : k ^ 0x7FFFFFFF); }
+
+__device__ __forceinline__ float wave_min(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+// chunk c = (node of the level, first position in the node, positions, 0)
+__global__ void k_big_init(int* __restrict__ big, int count) {
+  int* w = big + (size_t)kBigWords * blockIdx.x;
+  for (int i = threadIdx.x; i < kBigWords; i += blockDim.x) {
+    int v = 0;
+    if (i < oHist) v = (i % 2 == 0) ? fkey(INFINITY) : fkey(-INFINITY);
+    else if (i >= oCand && i < oCut) v = ((i - oCand) % 2 == 0) ? fkey(INFINITY) : fkey(-INFINITY);
+    w[i] = v;
+  }
+}
+
+__global__ __launch_bounds__(kBvhThreads) void k_big_bounds(const float* __restrict__ pts, int nE,
+                                                             const int4* __restrict__ node, int lb,
+                                                             const int* __restrict__ perm,
+                                                             const int4* __restrict__ chunks, int* __restrict__ big) {
+  const int4 ch = chunks[blockIdx.x];
+  const int s = node[lb + ch.x].x + ch.y;
+  int* w = big + (size_t)kBigWords * ch.x;
+  for (int a = 0; a < 6; ++a) {
+    float mn = INFINITY, mx = -INFINITY;
+    for (int i = threadIdx.x; i < ch.z; i += kBvhThreads) {
+      const float v = pts[(size_t)a * nE + perm[s + i]];
+      mn = fminf(mn, v);
+      mx = fmaxf(mx, v);
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if (threadIdx.x % 64 == 0) {
+      atomicMin(w + oBox + 2 * a, fkey(mn));
+      atomicMax(w + oBox + 2 * a + 1, fkey(mx));
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBvhThreads) void k_big_hist(const float* __restrict__ pts, int nE,
+                                                           const int4* __restrict__ node, int lb,
+                                                           const int* __restrict__ perm,
+                                                           const int4* __restrict__ chunks, int* __restrict__ big) {
+  __shared__ unsigned hist[6][kBins];
+  const int4 ch = chunks[blockIdx.x];
+  const int s = node[lb + ch.x].x + ch.y;
+  int* w = big + (size_t)kBigWords * ch.x;
+  for (int i = threadIdx.x; i < 6 * kBins; i += kBvhThreads) hist[i / kBins][i % kBins] = 0u;
+  __syncthreads();
+  for (int i = threadIdx.x; i < ch.z; i += kBvhThreads) {
+    const int I = perm[s + i];
+    for (int a = 0; a < 6; ++a) {
+      const float lo = fval(w[oBox + 2 * a]), hi = fval(w[oBox + 2 * a + 1]);
+      const float wd = hi - lo;
+      if (!(wd > 0.f)) continue;
+      atomicAdd(&hist[a][bin_of(pts[(size_t)a * nE + I], lo, kBins / wd)], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 6 * kBins; i += kBvhThreads)
+    if (hist[i / kBins][i % kBins]) atomicAdd(w + oHist + i, (int)hist[i / kBins][i % kBins]);
+}
+
+// per node: the balanced cut of each axis (as k_bvh_split)
+__global__ void k_big_cut(const int4* __restrict__ node, int lb, int* __restrict__ big) {
+  const int a = threadIdx.x;
+  if (a >= 6) return;
+  int* w = big + (size_t)kBigWords * blockIdx.x;
+  const int n = node[lb + blockIdx.x].y;
+  const float lo = fval(w[oBox + 2 * a]), hi = fval(w[oBox + 2 * a + 1]);
+  int run = 0, c = -1, nl = 0;
+  if (hi - lo > 0.f) {
+    for (int b = 0; b < kBins - 1; ++b) {
+      run += w[oHist + a * kBins + b];
+      if (run >= n / 2) {
+        c = b + 1;
+        nl = run;
+        break;
+      }
+    }
+    if (c > 0 && (nl == 0 || nl == n)) c = -1;
+  }
+  w[oCut + a] = c;
+  w[oNl + a] = nl;
+}
+
+// the two child boxes of candidate axis blockIdx.y on the chunk's positions
+__global__ __launch_bounds__(kBvhThreads) void k_big_cand(const float* __restrict__ pts, int nE,
+                                                           const int4* __restrict__ node, int lb,
+                                                           const int* __restrict__ perm,
+                                                           const int4* __restrict__ chunks, int* __restrict__ big) {
+  const int4 ch = chunks[blockIdx.x];
+  const int a = blockIdx.y;
+  int* w = big + (size_t)kBigWords * ch.x;
+  const int cut = w[oCut + a];
+  if (cut < 0) return;  // uniform per workgroup
+  const int s = node[lb + ch.x].x + ch.y;
+  const float lo = fval(w[oBox + 2 * a]), hi = fval(w[oBox + 2 * a + 1]);
+  const float inv_w = kBins / (hi - lo);
+  float lmn[6], lmx[6], rmn[6], rmx[6];
+  for (int d = 0; d < 6; ++d) {
+    lmn[d] = rmn[d] = INFINITY;
+    lmx[d] = rmx[d] = -INFINITY;
+  }
+  for (int i = threadIdx.x; i < ch.z; i += kBvhThreads) {
+    const int I = perm[s + i];
+    const bool left = bin_of(pts[(size_t)a * nE + I], lo, inv_w) < cut;
+    for (int d = 0; d < 6; ++d) {
+      const float v = pts[(size_t)d * nE + I];
+      if (left) {
+        lmn[d] = fminf(lmn[d], v);
+        lmx[d] = fmaxf(lmx[d], v);
+      } else {
+        rmn[d] = fminf(rmn[d], v);
+        rmx[d] = fmaxf(rmx[d], v);
+      }
+    }
+  }
+  int* cw = w + oCand + a * 24;
+  for (int d = 0; d < 6; ++d) {
+    const float a0 = wave_min(lmn[d]), a1 = wave_max(lmx[d]), b0 = wave_min(rmn[d]), b1 = wave_max(rmx[d]);
+    if (threadIdx.x % 64 == 0) {
+      atomicMin(cw + 2 * d, fkey(a0));
+      atomicMax(cw + 2 * d + 1, fkey(a1));
+      atomicMin(cw + 12 + 2 * d, fkey(b0));
+      atomicMax(cw + 12 + 2 * d + 1, fkey(b1));
+    }
+  }
+}
+
+// per split node: costs, the chosen axis, the node record and the partition plan
+__global__ void k_big_choose_split(int4* __restrict__ node, int lb, int* __restrict__ big, int* __restrict__ split) {
+  if (threadIdx.x != 0) return;
+  const int k = blockIdx.x;
+  if (!split[k]) return;  // a leaf of this level, written by the host
+  int* w = big + (size_t)kBigWords * k;
+  const int4 nd = node[lb + k];
+  int b = -1;
+  float cb = 0.f;
+  for (int a = 0; a < 6; ++a) {
+    if (w[oCut + a] < 0) continue;
+    const int* cw = w + oCand + a * 24;
+    float dl = 0.f, dr = 0.f;
+    for (int d = 0; d < 6; ++d) {
+      const float a0 = fval(cw[2 * d]), a1 = fval(cw[2 * d + 1]);
+      const float b0 = fval(cw[12 + 2 * d]), b1 = fval(cw[12 + 2 * d + 1]);
+      dl += (a1 - a0) * (a1 - a0);
+      dr += (b1 - b0) * (b1 - b0);
+    }
+    const float c = dl + dr;
+    if (b < 0 || c < cb) {
+      b = a;
+      cb = c;
+    }
+  }
+  const int nl = (b >= 0) ? w[oNl + b] : nd.y / 2;  // no usable plane: the range in halves
+  w[oPlan] = b;
+  w[oPlan + 1] = nl;
+  if (b >= 0) {
+    const float lo = fval(w[oBox + 2 * b]), hi = fval(w[oBox + 2 * b + 1]);
+    w[oPlan + 2] = __float_as_int(lo);
+    w[oPlan + 3] = __float_as_int(kBins / (hi - lo));
+  }
+  split[k] = 1;
+  node[lb + k] = make_int4(nd.x, nd.y, 0, nl);
+}
+
+__device__ __forceinline__ int big_left(const float* __restrict__ pts, int nE, const int* w, int I, int pos) {
+  const int b = w[oPlan];
+  if (b < 0) return pos < w[oPlan + 1];
+  return bin_of(pts[(size_t)b * nE + I], __int_as_float(w[oPlan + 2]), __int_as_float(w[oPlan + 3])) < w[oCut + b];
+}
+
+// left positions per chunk into chunks[c].w
+__global__ __launch_bounds__(kBvhThreads) void k_big_count(const float* __restrict__ pts, int nE,
+                                                            const int4* __restrict__ node, int lb,
+                                                            const int* __restrict__ perm, int4* __restrict__ chunks,
+                                                            const int* __restrict__ big) {
+  __shared__ int sm[kBvhThreads / 64];
+  const int4 ch = chunks[blockIdx.x];
+  const int s = node[lb + ch.x].x + ch.y;
+  const int* w = big + (size_t)kBigWords * ch.x;
+  int cnt = 0;
+  for (int i = threadIdx.x; i < ch.z; i += kBvhThreads) cnt += big_left(pts, nE, w, perm[s + i], ch.y + i);
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+  if (threadIdx.x % 64 == 0) sm[threadIdx.x / 64] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < kBvhThreads / 64; ++k) t += sm[k];
+    chunks[blockIdx.x].w = t;
+  }
+}
+
+// stable partition of the chunk's positions into scratch: its left ones after
+// the left ones of the node's earlier chunks, its right ones likewise after nl
+__global__ __launch_bounds__(kBvhThreads) void k_big_scatter(const float* __restrict__ pts, int nE,
+                                                              const int4* __restrict__ node, int lb,
+                                                              const int* __restrict__ perm,
+                                                              const int4* __restrict__ chunks,
+                                                              const int* __restrict__ big, int* __restrict__ scratch) {
+  __shared__ int smi[kBvhThreads];
+  __shared__ int base_l;
+  const int4 ch = chunks[blockIdx.x];
+  const int4 nd = node[lb + ch.x];
+  const int* w = big + (size_t)kBigWords * ch.x;
+  const int nl = w[oPlan + 1];
+  const int tid = threadIdx.x;
+  if (tid == 0) {  // left positions of the node's chunks before this one (they precede it in the table)
+    int t = 0;
+    for (int c = blockIdx.x - 1; c >= 0 && chunks[c].x == ch.x; --c) t += chunks[c].w;
+    base_l = t;
+  }
+  __syncthreads();
+  int lbase = base_l, rbase = ch.y - base_l;
+  for (int c0 = 0; c0 < ch.z; c0 += kBvhThreads) {
+    const int i = c0 + tid;
+    int flag = 0, I = -1;
+    if (i < ch.z) {
+      I = perm[nd.x + ch.y + i];
+      flag = big_left(pts, nE, w, I, ch.y + i);
+    }
+    smi[tid] = flag;
+    __syncthreads();
+    for (int off = 1; off < kBvhThreads; off <<= 1) {
+      const int v = (tid >= off) ? smi[tid - off] : 0;
+      __syncthreads();
+      smi[tid] += v;
+      __syncthreads();
+    }
+    const int incl = smi[tid];
+    const int total = smi[kBvhThreads - 1];
+    const int cnt = min(kBvhThreads, ch.z - c0);
+    if (i < ch.z) {
+      if (flag) scratch[nd.x + lbase + incl - 1] = I;
+      else scratch[nd.x + nl + rbase + (i - c0) - incl] = I;
+    }
+    lbase += total;
+    rbase += cnt - total;
+    __syncthreads();
+  }
+}
+
+__global__ void k_big_copy(const int4* __restrict__ node, int lb, const int4* __restrict__ chunks,
+                           const int* __restrict__ scratch, int* __restrict__ perm) {
+  const int4 ch = chunks[blockIdx.x];
+  const int s = node[lb + ch.x].x + ch.y;
+  for (int i = threadIdx.x; i < ch.z; i += blockDim.x) perm[s + i] = scratch[s + i];
 }
 
 // Children of the level's split nodes: slots le + 2 * (rank among split nodes).
@@ -486,7 +765,9 @@ rc_status Bvh::ensure(int nE_) {
       !al((void**)&pts, sizeof(float) * 6 * (size_t)nE) || !al((void**)&node, sizeof(int4) * cap) ||
       !al((void**)&na, sizeof(float4) * cap) || !al((void**)&nb, sizeof(float4) * cap) ||
       !al((void**)&nr, sizeof(float2) * cap) || !al((void**)&split, sizeof(int) * cap) ||
-      !al((void**)&counter, sizeof(int) * 4) || !al((void**)&work, sizeof(unsigned long long) * 2)) {
+      !al((void**)&counter, sizeof(int) * 4) || !al((void**)&work, sizeof(unsigned long long) * 2) ||
+      !al((void**)&big, sizeof(int) * kBigWords * kBigMaxNodes) ||
+      !al((void**)&chunks, sizeof(int4) * (nE / kBigChunk + 2 * kBigMaxNodes))) {
     set_error("BVH allocation failed");
     return RC_ERR_NOMEM;
   }
@@ -494,16 +775,66 @@ rc_status Bvh::ensure(int nE_) {
 }
 
 void Bvh::release() {
-  void* ps[] = {perm, scratch, pts, node, na, nb, nr, split, counter, work};
+  void* ps[] = {perm, scratch, pts, node, na, nb, nr, split, counter, work, big, chunks};
   for (void* p : ps)
     if (p) hipFree(p);
-  perm = scratch = split = counter = nullptr;
+  perm = scratch = split = counter = big = nullptr;
+  chunks = nullptr;
   pts = nullptr;
   node = nullptr;
   na = nb = nullptr;
   nr = nullptr;
   work = nullptr;
   nE = 0;
+}
+
+// One top level by chunks (see k_big_*): nodes of at most `leaf` edges
+// become leaves as in k_bvh_split; the others are split by the chunked kernels.
+static rc_status split_top_level(Bvh& bvh, int nE, int lb, int count, int leaf, hipStream_t s) {
+  std::vector<int4> nodes(count);
+  RC_HIP(hipMemcpyAsync(nodes.data(), bvh.node + lb, sizeof(int4) * count, hipMemcpyDeviceToHost, s));
+  RC_HIP(hipStreamSynchronize(s));
+  std::vector<int4> chunks;
+  std::vector<int> flags(count, 0);
+  for (int k = 0; k < count; ++k) {
+    if (nodes[k].y <= leaf) {
+      nodes[k] = make_int4(nodes[k].x, nodes[k].y, -1, 0);
+      continue;
+    }
+    flags[k] = 1;
+    for (int o = 0; o < nodes[k].y; o += kBigChunk) chunks.push_back(make_int4(k, o, std::min(kBigChunk, nodes[k].y - o), 0));
+  }
+  if ((int)chunks.size() > nE / kBigChunk + 2 * kBigMaxNodes) {
+    set_error("BVH top-level chunk table overflow");
+    return RC_ERR_HIP;
+  }
+  // leaves of this level are written here; split nodes by k_big_choose
+  RC_HIP(hipMemcpyAsync(bvh.split, flags.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+  for (int k = 0; k < count; ++k)
+    if (!flags[k]) RC_HIP(hipMemcpyAsync(bvh.node + lb + k, &nodes[k], sizeof(int4), hipMemcpyHostToDevice, s));
+  const int nc = (int)chunks.size();
+  if (nc > 0) {
+    RC_HIP(hipMemcpyAsync(bvh.chunks, chunks.data(), sizeof(int4) * nc, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_big_init, dim3(count), dim3(256), 0, s, bvh.big, count);
+    hipLaunchKernelGGL(k_big_bounds, dim3(nc), dim3(kBvhThreads), 0, s, bvh.pts, nE, bvh.node, lb, bvh.perm,
+                       bvh.chunks, bvh.big);
+    hipLaunchKernelGGL(k_big_hist, dim3(nc), dim3(kBvhThreads), 0, s, bvh.pts, nE, bvh.node, lb, bvh.perm,
+                       bvh.chunks, bvh.big);
+    hipLaunchKernelGGL(k_big_cut, dim3(count), dim3(64), 0, s, bvh.node, lb, bvh.big);
+    hipLaunchKernelGGL(k_big_cand, dim3(nc, 6), dim3(kBvhThreads), 0, s, bvh.pts, nE, bvh.node, lb, bvh.perm,
+                       bvh.chunks, bvh.big);
+    // only the split nodes (a leaf has no chunks; its block exits on its flag)
+    hipLaunchKernelGGL(k_big_choose_split, dim3(count), dim3(64), 0, s, bvh.node, lb, bvh.big, bvh.split);
+    hipLaunchKernelGGL(k_big_count, dim3(nc), dim3(kBvhThreads), 0, s, bvh.pts, nE, bvh.node, lb, bvh.perm,
+                       bvh.chunks, bvh.big);
+    hipLaunchKernelGGL(k_big_scatter, dim3(nc), dim3(kBvhThreads), 0, s, bvh.pts, nE, bvh.node, lb, bvh.perm,
+                       bvh.chunks, bvh.big, bvh.scratch);
+    hipLaunchKernelGGL(k_big_copy, dim3(nc), dim3(256), 0, s, bvh.node, lb, bvh.chunks, bvh.scratch, bvh.perm);
+  }
+  RC_HIP(hipGetLastError());
+  // the host copies above read `nodes` and `flags`: finish them before the vectors go
+  RC_HIP(hipStreamSynchronize(s));
+  return RC_OK;
 }
 
 rc_status build_bvh(const Curve& c, Bvh& bvh, int leaf, hipStream_t s) {
@@ -519,8 +850,12 @@ rc_status build_bvh(const Curve& c, Bvh& bvh, int leaf, hipStream_t s) {
       set_error("BVH deeper or larger than expected");
       return RC_ERR_HIP;
     }
-    hipLaunchKernelGGL(k_bvh_split, dim3(count), dim3(kBvhThreads), 0, s, bvh.pts, nE, bvh.node, lb, bvh.perm,
-                       bvh.scratch, leaf, bvh.split);
+    if (count <= kBigMaxNodes && nE / count >= kBigNode) {
+      RC_TRY(split_top_level(bvh, nE, lb, count, leaf, s));
+    } else {
+      hipLaunchKernelGGL(k_bvh_split, dim3(count), dim3(kBvhThreads), 0, s, bvh.pts, nE, bvh.node, lb, bvh.perm,
+                         bvh.scratch, leaf, bvh.split);
+    }
     hipLaunchKernelGGL(k_bvh_children, dim3(1), dim3(1024), 0, s, bvh.node, lb, count, bvh.split, lb + count,
                        bvh.counter);
     int next = 0;

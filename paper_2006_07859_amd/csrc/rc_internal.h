@@ -248,6 +248,8 @@ struct Bvh {
   float4 *na = nullptr, *nb = nullptr;
   float2* nr = nullptr;
   unsigned long long* work = nullptr;  // far-field and near-field interaction counts of the last traversal
+  int* big = nullptr;                   // accumulators of the multi-workgroup split of the top levels
+  int4* chunks = nullptr;               // its chunk table
   rc_status ensure(int nE_);
   void release();
 };
@@ -281,6 +283,7 @@ rc_status launch_bct_apply(const Curve& c, const Bvh& bvh, Bct& bct, double alph
 // Builds the BVH of the curve's current FP32 geometry (nodes of at most leaf
 // edges; node data and the inverse permutation in bvh.scratch).
 rc_status build_bvh(const Curve& c, Bvh& bvh, int leaf, hipStream_t s);
+constexpr int kStepBhLeaf = 32;  // leaf size of the Barnes-Hut evaluations inside rc_step
 // Barnes-Hut energy and differential in FP32 (needs the FP32 geometry).
 rc_status launch_bh(const Curve& c, Bvh& bvh, double alpha, double beta, double theta, int leaf, double* energy,
                     double* dE, hipStream_t s);

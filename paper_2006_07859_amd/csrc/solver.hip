@@ -1267,6 +1267,10 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
                       const rc_solve_opts& so, LsResult* out) {
   hipStream_t s = c->stream;
   const int n3 = 3 * c->nV, k = c->cons.k;
+  if (!(ls.bh_theta >= 0.0 && ls.bh_theta < 0.5)) {
+    set_error("line search options: bh_theta must be 0 or lie in (0, 0.5)");
+    return RC_ERR_ARG;
+  }
   // scal[16] keeps |g|^2 for the trial points; the solvers use scal[0..15]
   vec_dot(g, g, n3, c->red, c->scal + 16, s);
   vec_dot(dE, g, n3, c->red, c->scal + 17, s);
@@ -1341,7 +1345,10 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
     any_projected |= ok;
     if (ok) {
       RC_TRY(load_geometry(c, c->trial));
-      RC_TRY(launch_tpe(c->curve, c->alpha, c->beta, c->dtype, false, c->scal + 18, nullptr, s));
+      if (ls.bh_theta > 0.0)  // the Barnes-Hut energy (its differential goes to the free PCG buffer q)
+        RC_TRY(launch_bh(c->curve, c->bvh, c->alpha, c->beta, ls.bh_theta, kStepBhLeaf, c->scal + 18, c->q, s));
+      else
+        RC_TRY(launch_tpe(c->curve, c->alpha, c->beta, c->dtype, false, c->scal + 18, nullptr, s));
       double E1;
       RC_TRY(fetch(c, c->scal + 18, &E1, 1));
       if (std::isfinite(E1) && E1 <= E0 - ls.c_armijo * tau * slope) {
