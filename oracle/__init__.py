@@ -20,8 +20,10 @@ Modules
                  constraint projection, and the backtracking step (Sec. 4.3,
                  4.4, App. B.3.3-B.3.4).
 ``obstacle``     sphere-obstacle surface potential in closed form (Sec. 7.1).
+``penalties``    total-length, length-difference and field penalties (Sec. 7.1).
 ``ccd``          first collision time of a curve moving along a direction
                  (Sec. 4.4, time stepping).
-``learned``      the learned multilevel preconditioner's network, features and
-                 loss (not in the paper; its hierarchy follows App. B.3.1-B.3.2).
+``learned``      the learned multigrid smoother weights: network, features,
+                 targets and loss (not in the paper; its hierarchy follows
+                 App. B.3.1-B.3.2).
 """
