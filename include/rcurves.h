@@ -418,6 +418,16 @@ rc_status rc_lowp_apply(rc_ctx* ctx, const double* X, double* Y, int32_t f32);
  * edge midpoint on or inside the sphere gives an infinite energy. */
 rc_status rc_set_obstacle(rc_ctx* ctx, const double* center_h, double radius, double weight);
 
+/* Penalties of Sec. 7.1, added to every energy and differential of the
+ * context's all-pairs evaluations (rc_energy, rc_differential, rc_step
+ * without bh_theta, and the line search): w_length sum_I l_I (total length),
+ * w_diff sum over vertices of degree two of (l_I - l_J)^2 with I, J the
+ * vertex's edges (length difference), and w_field sum_I l_I |T_I x X|^2 for
+ * the constant unit field X = field_h / |field_h| (field potential; field_h
+ * host double[3], read only when w_field > 0).  Weights finite and >= 0
+ * (else RC_ERR_ARG); all zero removes them.  Not for batch contexts. */
+rc_status rc_set_penalties(rc_ctx* ctx, double w_length, double w_diff, double w_field, const double* field_h);
+
 /* ------------------------------------------------------------------------
  * Batches: many independent curve networks ("instances", e.g. packings of
  * closed loops) in one context.  Pair sums (energy, differential, operator)

@@ -32,6 +32,7 @@ EXPORTED = [
     "rc_set_constraints", "rc_constraint_values", "rc_constraint_count", "rc_project", "rc_sobolev_gradient",
     "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_bh_last_work", "rc_midpoint_differential",
     "rc_profile_enable", "rc_profile_read", "rc_lowp_assemble", "rc_lowp_apply", "rc_set_obstacle",
+    "rc_set_penalties",
     "rc_create_batch", "rc_batch_size", "rc_batch_energies", "rc_batch_tiling", "rc_default_batch_opts",
     "rc_batch_set_constraints", "rc_batch_gradient", "rc_batch_step", "rc_batch_pcg_state", "rc_batch_autotune",
     "rc_batch_sobolev_apply", "rc_mlp_n_params", "rc_mlp_create", "rc_mlp_destroy", "rc_mlp_get", "rc_mlp_set", "rc_mlp_forward",
@@ -124,6 +125,7 @@ def load():
         "rc_profile_read": (I32, [P, I32, C.POINTER(D), C.POINTER(I32)]),
         "rc_lowp_assemble": (I32, [P, P, I32, I32, I32]),
         "rc_set_obstacle": (I32, [P, P, D, D]),
+        "rc_set_penalties": (I32, [P, D, D, D, P]),
         "rc_create_batch": (I32, [I32, P, I32, I32, P, D, D, I32, P, P]),
         "rc_batch_size": (I32, [P]),
         "rc_batch_energies": (I32, [P, P, P, P]),
@@ -379,6 +381,11 @@ class Context:
     def rc_set_obstacle(self, center, radius, weight=1.0):
         self._c = (C.c_double * 3)(*[float(v) for v in center])
         _check(load().rc_set_obstacle(self.h, C.cast(self._c, C.c_void_p), float(radius), float(weight)))
+
+    def rc_set_penalties(self, w_length=0.0, w_diff=0.0, w_field=0.0, field=(0.0, 0.0, 1.0)):
+        self._f = (C.c_double * 3)(*[float(v) for v in field])
+        _check(load().rc_set_penalties(self.h, float(w_length), float(w_diff), float(w_field),
+                                       C.cast(self._f, C.c_void_p)))
 
     def rc_bh_last_work(self):
         f, n, nodes, depth = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32()

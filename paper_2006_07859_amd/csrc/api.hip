@@ -469,6 +469,10 @@ rc_status rc_step(rc_ctx* c, double* gamma, const rc_solve_opts* so, const rc_ls
     set_error("rc_step: bh_theta must be 0 or lie in (0, 0.5)");
     return RC_ERR_ARG;
   }
+  if (l.bh_theta > 0.0 && (c->curve.pen.on || c->curve.obstacle.on)) {
+    set_error("rc_step: the Barnes-Hut evaluation (bh_theta > 0) carries no penalties or obstacle");
+    return RC_ERR_UNSUPPORTED;
+  }
   hipStream_t s = c->stream;
   // dE and g live in buffers that no solver routine touches
   double* dEb = c->dEs;
@@ -658,6 +662,34 @@ extern "C" rc_status rc_set_obstacle(rc_ctx* c, const double* center_h, double r
   o.R = radius;
   o.p = c->beta - c->alpha;
   o.w = weight;
+  return RC_OK;
+}
+
+extern "C" rc_status rc_set_penalties(rc_ctx* c, double w_length, double w_diff, double w_field,
+                                     const double* field_h) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_set_penalties"));
+  if (!std::isfinite(w_length) || !std::isfinite(w_diff) || !std::isfinite(w_field) || w_length < 0.0 ||
+      w_diff < 0.0 || w_field < 0.0) {
+    set_error("rc_set_penalties: weights must be finite and >= 0");
+    return RC_ERR_ARG;
+  }
+  Penalties& p = c->curve.pen;
+  double X[3] = {0.0, 0.0, 1.0};
+  if (w_field > 0.0) {
+    RC_TRY(check_ptrs({field_h}));
+    const double n = std::sqrt(field_h[0] * field_h[0] + field_h[1] * field_h[1] + field_h[2] * field_h[2]);
+    if (!(n > 0.0) || !std::isfinite(n)) {
+      set_error("rc_set_penalties: the field direction must be a nonzero finite vector");
+      return RC_ERR_ARG;
+    }
+    for (int k = 0; k < 3; ++k) X[k] = field_h[k] / n;
+  }
+  p.w_len = w_length;
+  p.w_diff = w_diff;
+  p.w_field = w_field;
+  for (int k = 0; k < 3; ++k) p.X[k] = X[k];
+  p.on = w_length > 0.0 || w_diff > 0.0 || w_field > 0.0;
   return RC_OK;
 }
 

@@ -853,9 +853,66 @@ __global__ void k_obstacle(const V4<double>* __restrict__ GA, const V4<double>* 
 }
 
 // ---------------------------------------------------------------------------
+// penalties (Sec. 7.1): per edge I, with e = l T its edge vector,
+//   total length   w_len l                    d/de = w_len T
+//   field          w_field (l - (e.X)^2 / l)  d/de = w_field (T - 2 (T.X) X + (T.X)^2 T)
+//   length diff.   half of (l_I - l_J)^2 at each endpoint v of degree two (J the other edge at v),
+//                  d/de = 2 sum_v (l_I - l_J) T   (the J side comes from edge J's own thread)
+// and d/d(gamma_i2) = d/de, d/d(gamma_i1) = -d/de.
+// ---------------------------------------------------------------------------
+__global__ void k_penalties(const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GT,
+                            const int2* __restrict__ edges, const int* __restrict__ inc_off,
+                            const int* __restrict__ inc, int nE, double w_len, double w_diff, double w_field,
+                            double X0, double X1, double X2, int grad, double* __restrict__ edge_out) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nE) return;
+  const double l = GA[I].w;
+  const V4<double> t = GT[I];
+  double E = w_len * l, gl = w_len;  // gl: coefficient of T in d/de
+  if (w_diff != 0.0) {
+    const int2 e = edges[I];
+    const int ends[2] = {e.x, e.y};
+    for (int k = 0; k < 2; ++k) {
+      const int v = ends[k];
+      if (inc_off[v + 1] - inc_off[v] != 2) continue;
+      const int J0 = inc[inc_off[v]] >> 1, J1 = inc[inc_off[v] + 1] >> 1;
+      const int J = J0 == I ? J1 : J0;
+      const double d = l - GA[J].w;
+      E += 0.5 * w_diff * d * d;
+      gl += 2.0 * w_diff * d;
+    }
+  }
+  double g[3] = {gl * t.x, gl * t.y, gl * t.z};
+  if (w_field != 0.0) {
+    const double tx = t.x * X0 + t.y * X1 + t.z * X2;
+    E += w_field * l * (1.0 - tx * tx);
+    g[0] += w_field * (t.x - 2.0 * tx * X0 + tx * tx * t.x);
+    g[1] += w_field * (t.y - 2.0 * tx * X1 + tx * tx * t.y);
+    g[2] += w_field * (t.z - 2.0 * tx * X2 + tx * tx * t.z);
+  }
+  double* o = edge_out + 8 * (size_t)I;
+  o[0] += E;
+  if (!grad) return;
+  for (int c = 0; c < 3; ++c) {
+    o[1 + c] -= g[c];
+    o[4 + c] += g[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+rc_status launch_penalties(const Curve& c, bool grad, hipStream_t s) {
+  if (!c.pen.on) return RC_OK;
+  const Penalties& p = c.pen;
+  hipLaunchKernelGGL(k_penalties, dim3(cdiv(c.nE, 256)), dim3(256), 0, s, (const V4<double>*)c.gd.a,
+                     (const V4<double>*)c.gd.t, (const int2*)c.edges, (const int*)c.inc_off, (const int*)c.inc, c.nE,
+                     p.w_len, p.w_diff, p.w_field, p.X[0], p.X[1], p.X[2], grad ? 1 : 0, c.edge_out);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
 
 rc_status launch_geometry(const Curve& c, const double* gamma, rc_dtype prec, hipStream_t s) {
   dim3 g(cdiv(c.nE, 256)), b(256);
@@ -947,6 +1004,7 @@ rc_status launch_tpe(const Curve& c, double alpha, double beta, rc_dtype prec, b
     hipLaunchKernelGGL(k_obstacle, dim3(cdiv(c.nE, 256)), dim3(256), 0, s, c.gd.a, c.gd.b, c.gd.t, c.nE, o.c[0],
                        o.c[1], o.c[2], o.R, o.p, o.w, grad ? 1 : 0, c.edge_out);
   }
+  RC_TRY(launch_penalties(c, grad, s));
   if (grad && dE)
     hipLaunchKernelGGL(k_gather_vertex, dim3(cdiv(c.nV, 256)), dim3(256), 0, s, c.edge_out, c.inc_off,
                        c.inc, c.nV, dE, c.status);

@@ -405,6 +405,7 @@ rc_status launch_tpe_vp_finish(const Curve& c, double beta, bool grad, double* d
   hipLaunchKernelGGL(k_vp_edge, dim3(vp_cdiv(c.nE, 256)), dim3(256), 0, s, (const double*)c.vout,
                      (const int2*)c.edges, (const int*)c.inc_off, (const int*)c.inc, (const V4<double>*)c.gd.a,
                      (const V4<double>*)c.gd.t, c.nE, grad ? 1 : 0, c.edge_out);
+  RC_TRY(launch_penalties(c, grad, s));
   if (grad && dE)
     hipLaunchKernelGGL(k_vp_gather, dim3(vp_cdiv(c.nV, 256)), dim3(256), 0, s, (const double*)c.vout,
                        (const double*)c.edge_out, (const int*)c.inc_off, (const int*)c.inc, c.nV, dE, c.status);

@@ -131,6 +131,15 @@ struct Obstacle {
   double R = 0, p = 0, w = 0;
 };
 
+// Penalties of Sec. 7.1 added to the energy: w_len sum_I l_I (total length),
+// w_diff sum over degree-2 vertices of (l_I - l_J)^2 (length difference) and
+// w_field sum_I l_I |T_I x X|^2 for a constant unit vector X (field potential).
+struct Penalties {
+  bool on = false;
+  double w_len = 0, w_diff = 0, w_field = 0;
+  double X[3] = {0, 0, 1};
+};
+
 // A curve network on the device (the finest level, or a multigrid level).
 struct Curve {
   int nV = 0, nE = 0;
@@ -189,6 +198,7 @@ struct Curve {
   int* counter = nullptr;
   const int* inst_mask = nullptr;  // when set, work items of instances with mask 0 are skipped
   Obstacle obstacle;               // applied by launch_tpe when on
+  Penalties pen;                   // applied by launch_tpe when on
 
   rc_status init(int nV_, int nE_, const int* edges_h);
   rc_status set_instances(int n_inst_, const int* voff_h);
@@ -234,6 +244,8 @@ rc_status launch_first_collision(const Curve& c, const double* gamma, const doub
 // the gather into dE.
 void launch_vertex_geometry(const Curve& c, const double* gamma, hipStream_t s);
 rc_status launch_tpe_vp_pairs(const Curve& c, double beta, bool grad, hipStream_t s);
+// Adds the penalties (c.pen) to the per-edge energy / endpoint-derivative slots of edge_out.
+rc_status launch_penalties(const Curve& c, bool grad, hipStream_t s);
 rc_status launch_tpe_vp_finish(const Curve& c, double beta, bool grad, double* dE, hipStream_t s);
 // Shared tail of the edge-midpoint kernels: sums nparts chunks of the
 // 10-slot partials, writes energy and dE.
