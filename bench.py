@@ -46,6 +46,10 @@ FLOPS_PER_PAIR_SOB = 100   # operator, algorithmic
 # Edge-midpoint kernel k(x_I, x_J, T_I) l_I l_J and its partials for one ordered pair (Barnes-Hut leaf pairs
 # and cluster interactions): 86 FP32 flops and 2 transcendentals as evaluated.
 FLOPS_PER_PAIR_MID = 86
+# block cluster tree near field, per edge pair (FP64): difference, squared distance, the two cross
+# products and their squares (~40), the powers of |d| from an FP32 estimate and Newton steps (~12),
+# the two kernels (~8), and 14 accumulated products (28)
+FLOPS_PER_NEAR_PAIR_BCT = 90
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed); the non-packed issue limit is half
 PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
@@ -216,12 +220,13 @@ def main():
     ap.add_argument("--edges", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="default workload: skip the plain-multigrid comparison")
-    ap.add_argument("--workload", default="step", choices=["step", "bh", "precision", "batch", "learned"],
+    ap.add_argument("--workload", default="step", choices=["step", "bh", "precision", "batch", "learned", "large"],
                     help="step: projected Sobolev steps on the 16,384-edge knot (default); "
                          "bh: Barnes-Hut energy+differential on a 262,144-edge knot; "
                          "precision: assembled 16-bit Sobolev block and a solve to 1e-8 on a 32,768-edge knot; "
                          "batch: 512 packing instances, one captured step; "
-                         "learned: train the learned V-cycle smoother weights, then compare PCG preconditioners")
+                         "learned: train the learned V-cycle smoother weights, then compare PCG preconditioners; "
+                         "large: projected steps on a 262,144-edge knot with Barnes-Hut and the block cluster tree")
     ap.add_argument("--train-steps", type=int, default=1500, help="Adam steps of the learned smoother weights")
     ap.add_argument("--train-knots", type=int, default=24, help="knots whose flows give the training snapshots")
     ap.add_argument("--train-snapshots", type=int, default=40, help="snapshots per training knot")
@@ -242,6 +247,8 @@ def main():
         return bench_batch(args)
     if args.workload == "learned":
         return bench_learned(args)
+    if args.workload == "large":
+        return bench_large(args)
 
     import numpy as np
     import torch
@@ -463,6 +470,90 @@ def bench_bh(args):
         "roofline": roofline,
         "exact_midpoint_ms": Tm * 1e3,
         "error_vs_exact_midpoint": {"energy_rel": err_E, "differential_rel": err_G},
+    }
+    ctx.close()
+    print(json.dumps(out))
+
+
+def bench_large(args):
+    """Projected Sobolev steps at 262,144 edges with the paper's large-curve
+    approximations (App. B): Barnes-Hut energy and differential and trial
+    energies (theta 0.25), multigrid PCG to a 1e-6 FP64 residual on block
+    cluster tree operators (theta 0.25, every level of 16,384+ vertices),
+    barycenter and edge-length constraints."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2006_07859_amd import (RC_C_BARYCENTER, RC_C_EDGE_LENGTH, RC_F32, RC_SOLVE_PCG_MG, Context,
+                                      default_ls_opts, default_solve_opts)
+
+    n = 262144 if args.edges == 16384 else args.edges
+    alpha, beta, theta = 2.0, 4.5, 0.25
+    g, e, _ = gen.fourier_knot(n, seed=0)
+    g = gen.round_to_f32(g)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    ctx = Context(n, e, alpha, beta, RC_F32)
+    gamma = dev(g)
+    ctx.rc_set_constraints(RC_C_BARYCENTER | RC_C_EDGE_LENGTH, gamma)
+    so = default_solve_opts(solver=RC_SOLVE_PCG_MG, tol=1e-6, mg_min_vertices=256, cheb_degree=2, op_f64=1,
+                            max_iter=200, bct_theta=theta, bct_min_vertices=16384)
+    ls = default_ls_opts(bh_theta=theta)
+    for _ in range(args.warmup):
+        ctx.rc_step(gamma, so=so, ls=ls)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        st = ctx.rc_step(gamma, so=so, ls=ls)
+        stats.append(st)
+        print(f"[bench] large step {k}: E {st['energy']:.8g} -> {st['energy_new']:.8g}, pcg {st['iterations']} it, "
+              f"res {st['residual']:.1e}, tau {st['tau']:.3g}, eval {st['t_eval_ms']:.1f} ms, solve "
+              f"{st['t_solve_ms']:.1f} ms, search {st['t_search_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T = (time.perf_counter() - t0) / args.steps
+    # the block cluster tree product at the final curve, timed alone on the context's stream
+    ctx.rc_bct_build(gamma, theta, 32)
+    bstats = ctx.rc_bct_stats()
+    X = dev(np.random.default_rng(3).normal(size=(n, 3)))
+    Y = torch.zeros_like(X)
+    ctx.rc_sobolev_apply_bct(gamma, X, Y)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(10):
+        ctx.rc_sobolev_apply_bct(gamma, X, Y)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    prod_ms = ev0.elapsed_time(ev1) / 10
+    # the near field dominates the product: ~100 FP64 flops per near pair (kernel pair, 14 products)
+    near_flops = FLOPS_PER_NEAR_PAIR_BCT * bstats["near_pairs"]
+    ach = near_flops / (prod_ms * 1e-3) / 1e12
+    out = {
+        "metric": "projected Sobolev steps/s (262,144-edge knot, Barnes-Hut + block cluster tree)",
+        "value": 1.0 / T,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"fourier knot, {n} edges, (alpha,beta)=(2,4.5), barycenter+edge-length "
+                               "constraints, Barnes-Hut energy/differential theta=0.25, multigrid PCG to 1e-6 on "
+                               "block cluster tree operators theta=0.25 (levels of 16,384+ vertices)", "edges": n},
+        "per_step": {"iterations": [s["iterations"] for s in stats], "tau": [s["tau"] for s in stats],
+                     "t_eval_ms": [round(s["t_eval_ms"], 2) for s in stats],
+                     "t_solve_ms": [round(s["t_solve_ms"], 1) for s in stats],
+                     "t_search_ms": [round(s["t_search_ms"], 1) for s in stats]},
+        "bct": bstats,
+        "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "kernel": "block cluster tree product (all its launches; near-field FP64 flops)",
+                     "avg_launch_ms": round(prod_ms, 4), "flops_per_near_pair": FLOPS_PER_NEAR_PAIR_BCT},
     }
     ctx.close()
     print(json.dumps(out))
