@@ -497,7 +497,7 @@ def bench_large(args):
     gamma = dev(g)
     ctx.rc_set_constraints(RC_C_BARYCENTER | RC_C_EDGE_LENGTH, gamma)
     so = default_solve_opts(solver=RC_SOLVE_PCG_MG, tol=1e-6, mg_min_vertices=256, cheb_degree=2, op_f64=1,
-                            max_iter=200, bct_theta=theta, bct_min_vertices=16384)
+                            max_iter=200, bct_theta=theta, bct_min_vertices=8192)
     ls = default_ls_opts(bh_theta=theta)
     for _ in range(args.warmup):
         ctx.rc_step(gamma, so=so, ls=ls)
@@ -544,7 +544,7 @@ def bench_large(args):
         "data": "synthetic",
         "config": {"workload": f"fourier knot, {n} edges, (alpha,beta)=(2,4.5), barycenter+edge-length "
                                "constraints, Barnes-Hut energy/differential theta=0.25, multigrid PCG to 1e-6 on "
-                               "block cluster tree operators theta=0.25 (levels of 16,384+ vertices)", "edges": n},
+                               "block cluster tree operators theta=0.25 (levels of 8,192+ vertices)", "edges": n},
         "per_step": {"iterations": [s["iterations"] for s in stats], "tau": [s["tau"] for s in stats],
                      "t_eval_ms": [round(s["t_eval_ms"], 2) for s in stats],
                      "t_solve_ms": [round(s["t_solve_ms"], 1) for s in stats],

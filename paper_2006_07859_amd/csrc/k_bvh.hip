@@ -36,7 +36,7 @@ constexpr int kBins = 64;
 constexpr int kStack = 64;
 // top-level split over many workgroups: levels of at most kBigMaxNodes nodes
 // whose mean size is at least kBigNode, in chunks of kBigChunk positions
-constexpr int kBigMaxNodes = 64, kBigNode = 8192, kBigChunk = 4096, kBigWords = 640;
+constexpr int kBigMaxNodes = 1024, kBigNode = 2048, kBigChunk = 4096, kBigWords = 640;
 
 // tangent-points, SoA [6][nE]: T (3) then midpoint x (3)
 __global__ void k_tangent_points(const V4<float>* __restrict__ GA, const V4<float>* __restrict__ GB,

@@ -16,7 +16,7 @@ void vec_trial(const double* gamma, const double* g, const double* gg, double ta
 // Tridiagonal systems, block-partitioned (see k_linalg.hip): kSpThreads
 // threads per block of S = kSpThreads m rows, at most kSpMaxB blocks.
 constexpr int kTriThreads = 1024, kTriWaves = kTriThreads / 64;
-constexpr int kSpThreads = 256, kSpWaves = kSpThreads / 64, kSpMaxM = 8, kSpMaxB = 512;
+constexpr int kSpThreads = 256, kSpWaves = kSpThreads / 64, kSpMaxM = 16, kSpMaxB = 512;
 struct TriBlocks {
   int n = 0;   // rows
   int S = 1;   // rows per block
