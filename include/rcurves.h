@@ -91,11 +91,17 @@ typedef enum {
   RC_SOLVE_DENSE = 0,    /* assembled FP64 A, Cholesky of Abar + C^T C, Schur complement */
   RC_SOLVE_PCG_JACOBI = 1, /* matrix-free projected PCG, Jacobi preconditioner */
   RC_SOLVE_PCG_MG = 2,   /* matrix-free projected PCG, multigrid V-cycle preconditioner */
-  RC_SOLVE_PCG_LEARNED = 4 /* the multigrid V-cycle with learned smoother weights: the MLP attached by
+  RC_SOLVE_PCG_LEARNED = 4, /* the multigrid V-cycle with learned smoother weights: the MLP attached by
                               rc_learned_attach predicts a diagonal scaling per vertex that places the
                               top of the smoother's spectrum at 1, which fixes the Chebyshev interval (no
                               spectral estimate); one closed loop numbered along itself.  (The value 3
                               is not a solver kind.) */
+  RC_SOLVE_MG_FMG = 5      /* the paper's standalone multigrid (App. B.3.1): full-multigrid initialisation
+                              (right-hand side coarsened to the coarsest level, direct saddle solve there,
+                              prolonged level by level with smoothing after each refinement), then
+                              V-cycles with a projected CG smoother (cheb_degree CG steps per visit) until
+                              the relative residual reaches tol; no outer Krylov method.  rc_stats
+                              .iterations counts the V-cycles (the initialisation not included) */
 } rc_solver;
 
 typedef struct {
@@ -104,7 +110,7 @@ typedef struct {
   int32_t max_iter;      /* PCG iterations (all restarts together) */
   int32_t replace_every; /* FP64 true-residual replacement period (0 = only at convergence) */
   int32_t mg_min_vertices; /* coarsest multigrid level size (vertices per loop, total) */
-  int32_t cheb_degree;   /* Chebyshev smoothing steps per V-cycle visit */
+  int32_t cheb_degree;   /* smoothing steps per V-cycle visit (Chebyshev degree; CG steps for RC_SOLVE_MG_FMG) */
   int32_t op_f64;        /* 1 = the PCG operator runs in FP64 even when dtype is F32 */
   int32_t lowp;          /* precision path (see rc_lowp_assemble): 0 = off; 1 = BF16, 2 = FP16
                             assembled blocks in the multigrid smoothers of the finest levels, the

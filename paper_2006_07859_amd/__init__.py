@@ -16,6 +16,7 @@ from ._lib import (  # noqa: F401
     RC_SOLVE_PCG_JACOBI,
     RC_SOLVE_PCG_LEARNED,
     RC_SOLVE_PCG_MG,
+    RC_SOLVE_MG_FMG,
     Batch,
     Context,
     Mlp,

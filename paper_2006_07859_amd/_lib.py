@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "librcurves.so")
 
 RC_F64, RC_F32 = 0, 1
 RC_C_BARYCENTER, RC_C_TOTAL_LENGTH, RC_C_EDGE_LENGTH = 1, 2, 4
-RC_SOLVE_DENSE, RC_SOLVE_PCG_JACOBI, RC_SOLVE_PCG_MG, RC_SOLVE_PCG_LEARNED = 0, 1, 2, 4
+RC_SOLVE_DENSE, RC_SOLVE_PCG_JACOBI, RC_SOLVE_PCG_MG, RC_SOLVE_PCG_LEARNED, RC_SOLVE_MG_FMG = 0, 1, 2, 4, 5
 
 STATUS = {
     0: "RC_OK", 1: "RC_ERR_ARG", 2: "RC_ERR_PARAM_RANGE", 3: "RC_ERR_DEGENERATE", 4: "RC_ERR_NONFINITE",

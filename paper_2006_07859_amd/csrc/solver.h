@@ -171,6 +171,7 @@ struct rc_ctx {
   double* learn_scratch = nullptr;
   float *learn_X = nullptr, *learn_Y = nullptr;
   bool mg_learned = false;  // the V-cycle's smoothers take the attached MLP's weights
+  bool mg_cg = false;       // the standalone multigrid with CG smoothing (no Chebyshev interval)
 };
 
 struct rc_mlp {

@@ -170,6 +170,11 @@ __global__ void k_negate(const double* __restrict__ in, double* __restrict__ out
   if (i < n) out[i] = -in[i];
 }
 
+__global__ void k_fill(double* __restrict__ x, int n, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
 __global__ void k_fill_pattern(double* __restrict__ x, int n, unsigned seed) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -831,6 +836,7 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
       st.lmax = 1.0;
       continue;
     }
+    if (c->mg_cg) continue;  // the CG smoother needs no spectral interval
     // lambda_max of the smoother's preconditioned operator (P D^-1 P A P, or M A with the
     // weighted projector M) by power iteration, warm-started from the last call's vector: at
     // most 12 iterations, stopping once the estimate moves by less than 1 % after at least 3
@@ -1132,7 +1138,7 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
 // entry points used by the C ABI
 // ---------------------------------------------------------------------------
 rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o) {
-  if (o.solver < RC_SOLVE_DENSE || o.solver > RC_SOLVE_PCG_LEARNED || o.solver == 3) {
+  if (o.solver < RC_SOLVE_DENSE || o.solver > RC_SOLVE_MG_FMG || o.solver == 3) {
     set_error("solve options: unknown solver kind");
     return RC_ERR_ARG;
   }
@@ -1146,7 +1152,8 @@ rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o)
   }
   c->lowp_levels = 0;
   if (o.bct_theta < 0.0 ||
-      (o.bct_theta > 0.0 && (o.lowp || (o.solver != RC_SOLVE_PCG_MG && o.solver != RC_SOLVE_PCG_LEARNED)))) {
+      (o.bct_theta > 0.0 &&
+       (o.lowp || (o.solver != RC_SOLVE_PCG_MG && o.solver != RC_SOLVE_PCG_LEARNED && o.solver != RC_SOLVE_MG_FMG)))) {
     set_error("solve options: the block-cluster-tree operator (bct_theta > 0) serves the multigrid solver "
               "without the precision path");
     return RC_ERR_ARG;
@@ -1167,6 +1174,7 @@ rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o)
   c->lowp_band = o.lowp_band;
   c->lowp_outer = o.lowp_outer;
   c->mg_learned = false;
+  c->mg_cg = o.solver == RC_SOLVE_MG_FMG;
   if (o.solver == RC_SOLVE_PCG_LEARNED) {
     if (!c->mlp) {
       set_error("learned smoother: no MLP attached (rc_learned_attach)");
@@ -1175,7 +1183,7 @@ rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o)
     RC_TRY(learn_prepare_levels(c, o.mg_min_vertices));
     c->mg_learned = true;
   }
-  if (o.solver == RC_SOLVE_PCG_MG || o.solver == RC_SOLVE_PCG_LEARNED) {
+  if (o.solver == RC_SOLVE_PCG_MG || o.solver == RC_SOLVE_PCG_LEARNED || o.solver == RC_SOLVE_MG_FMG) {
     if (c->mg_min != o.mg_min_vertices) {
       mg_free(c);
       c->mg_min = o.mg_min_vertices;
@@ -1228,6 +1236,181 @@ rc_status solve_gradient(rc_ctx* c, const double* gamma, const double* rhs, doub
   return st;
 }
 
+// ---------------------------------------------------------------------------
+// The paper's standalone multigrid (App. B.3.1): full-multigrid
+// initialisation, then V-cycles with a conjugate-gradient smoother on each
+// level's projected system P A_l P y = P b (App. B.3.3), until the relative
+// residual |P (b - A x)| / |P b| reaches the tolerance.  The smoother runs
+// with its scalars on the device (no host reads); being nonlinear it serves
+// this stationary iteration, not a Krylov preconditioner.
+// ---------------------------------------------------------------------------
+static constexpr int kCgScal = 32;  // scal[32 + 6 l ...]: the level's r.r (two slots), p.q, e.r, e.Ae
+
+// x += (num / den) e with the two scalars on the device (no step when den <= 0)
+__global__ void k_axpy_ratio(const double* __restrict__ num, const double* __restrict__ den,
+                             const double* __restrict__ e, double* __restrict__ x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = den[0] > 0.0 ? num[0] / den[0] : 0.0;
+  x[i] += a * e[i];
+}
+
+// `steps` CG steps on P A_l P y = P b from x (in range(P)); scratch st.r, st.d, st.t.
+static rc_status cg_smooth(rc_ctx* c, int l, double* x, const double* b, int steps) {
+  const Curve& cv = level_curve(c, l);
+  Cons& K = level_cons(c, l);
+  MGLevelState& st = c->mg[l];
+  hipStream_t s = c->stream;
+  const int n3 = 3 * cv.nV;
+  double* sc = c->scal + kCgScal + 6 * l;
+  RC_TRY(apply_level(c, l, x, st.t));
+  vec_copy(b, st.r, n3, s);
+  vec_axpby(-1.0, st.t, 1.0, st.r, n3, s);
+  cons_project(c, cv, K, st.r, st.r);  // r = P (b - A x)
+  vec_copy(st.r, st.d, n3, s);
+  vec_dot(st.r, st.r, n3, c->red, sc, s);
+  int par = 0;
+  for (int k = 0; k < steps; ++k) {
+    RC_TRY(apply_level(c, l, st.d, st.t));
+    cons_project(c, cv, K, st.t, st.t);  // q = P A p
+    vec_dot(st.d, st.t, n3, c->red, sc + 2, s);
+    hipLaunchKernelGGL(k_pcg_xr, dim3(cdiv(n3, 256)), dim3(256), 0, s, (const double*)(sc + par),
+                       (const double*)(sc + 2), (const double*)st.d, (const double*)st.t, x, st.r, n3);
+    if (k + 1 == steps) break;
+    vec_dot(st.r, st.r, n3, c->red, sc + (par ^ 1), s);
+    hipLaunchKernelGGL(k_pcg_p, dim3(cdiv(n3, 256)), dim3(256), 0, s, (const double*)(sc + (par ^ 1)),
+                       (const double*)(sc + par), (const double*)st.r, st.d, n3);
+    par ^= 1;
+  }
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+// x <- one V-cycle on level l for right-hand side b from the guess x.
+static rc_status vcycle_cg(rc_ctx* c, int l, const double* b, double* x, int steps) {
+  hipStream_t s = c->stream;
+  const int nl = (int)c->levels.size();
+  if (l == nl - 1) {
+    dense_solve(c, c->coarse, b, x);
+    return RC_OK;
+  }
+  const Curve& cv = level_curve(c, l);
+  Cons& K = level_cons(c, l);
+  MGLevelState& st = c->mg[l];
+  const int n3 = 3 * cv.nV;
+  RC_TRY(cg_smooth(c, l, x, b, steps));
+  RC_TRY(apply_level(c, l, x, st.t));
+  vec_copy(b, st.r, n3, s);
+  vec_axpby(-1.0, st.t, 1.0, st.r, n3, s);
+  cons_project(c, cv, K, st.r, st.r);  // r = P (b - A x)
+  Level& C = *c->levels[l + 1];
+  MGLevelState& sc = c->mg[l + 1];
+  hipLaunchKernelGGL(k_restrict, dim3(cdiv(C.curve.nV, 256)), dim3(256), 0, s, C.restr_off, C.restr_idx, C.prolong,
+                     C.curve.nV, st.r, sc.b);
+  hipLaunchKernelGGL(k_fill, dim3(cdiv(3 * C.curve.nV, 256)), dim3(256), 0, s, sc.x, 3 * C.curve.nV, 0.0);
+  RC_TRY(vcycle_cg(c, l + 1, sc.b, sc.x, steps));
+  hipLaunchKernelGGL(k_prolong, dim3(cdiv(cv.nV, 256)), dim3(256), 0, s, C.prolong, cv.nV, sc.x, st.t);
+  cons_project(c, cv, K, st.t, st.t);  // e = P J x_c
+  // the correction's step minimises the A-norm error along e: x += (e.r / e.A e) e (the rediscretised
+  // coarse operators over-correct, and the unit step diverges)
+  double* scl = c->scal + kCgScal + 6 * l;
+  RC_TRY(apply_level(c, l, st.t, st.d));
+  cons_project(c, cv, K, st.d, st.d);
+  vec_dot(st.t, st.r, n3, c->red, scl + 3, s);
+  vec_dot(st.t, st.d, n3, c->red, scl + 4, s);
+  hipLaunchKernelGGL(k_axpy_ratio, dim3(cdiv(n3, 256)), dim3(256), 0, s, (const double*)(scl + 3),
+                     (const double*)(scl + 4), (const double*)st.t, x, n3);
+  RC_TRY(cg_smooth(c, l, x, b, steps));
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
+static rc_status fmg_solve(rc_ctx* c, const double* b, double* x, const rc_solve_opts& o, int* iters_out,
+                           double* res_out) {
+  hipStream_t s = c->stream;
+  const int nl = (int)c->levels.size();
+  const int n3 = 3 * c->nV, steps = std::max(1, o.cheb_degree);
+  const rc_dtype op = o.op_f64 ? RC_F64 : c->dtype;
+  *iters_out = 0;
+  *res_out = 0.0;
+  if (kCgScal + 6 * nl > 128) {
+    set_error("standalone multigrid: too many levels for the smoother's device scalars");
+    return RC_ERR_UNSUPPORTED;
+  }
+  // finest right-hand side P b, restricted level by level (each level's own projection first)
+  double* b0 = c->tmp2;
+  cons_project(c, c->curve, c->cons, b, b0);
+  vec_dot(b0, b0, n3, c->red, c->scal, s);
+  double bb;
+  RC_TRY(fetch(c, c->scal, &bb, 1));
+  const double bn = std::sqrt(bb);
+  hipLaunchKernelGGL(k_fill, dim3(cdiv(n3, 256)), dim3(256), 0, s, x, n3, 0.0);
+  if (!(bn > 0)) return RC_OK;
+  for (int l = 1; l < nl; ++l) {
+    const double* bf = l == 1 ? b0 : c->mg[l - 1].b;
+    Level& C = *c->levels[l];
+    if (l > 1) {
+      const Curve& fv = level_curve(c, l - 1);
+      cons_project(c, fv, level_cons(c, l - 1), c->mg[l - 1].b, c->mg[l - 1].b);
+    }
+    hipLaunchKernelGGL(k_restrict, dim3(cdiv(C.curve.nV, 256)), dim3(256), 0, s, C.restr_off, C.restr_idx,
+                       C.prolong, C.curve.nV, bf, c->mg[l].b);
+  }
+  // direct solve on the coarsest level, then prolong and smooth level by level
+  double* xc = nl == 1 ? x : c->mg[nl - 1].x;
+  const double* bc = nl == 1 ? b0 : c->mg[nl - 1].b;
+  if (nl == 1) {
+    set_error("standalone multigrid: the curve has no coarser level (raise n or lower mg_min_vertices)");
+    return RC_ERR_UNSUPPORTED;
+  }
+  dense_solve(c, c->coarse, bc, xc);
+  for (int l = nl - 2; l >= 0; --l) {
+    const Curve& cv = level_curve(c, l);
+    double* xl = l == 0 ? x : c->mg[l].x;
+    const double* bl = l == 0 ? b0 : c->mg[l].b;
+    hipLaunchKernelGGL(k_prolong, dim3(cdiv(cv.nV, 256)), dim3(256), 0, s, c->levels[l + 1]->prolong, cv.nV,
+                       c->mg[l + 1].x, xl);
+    cons_project(c, cv, level_cons(c, l), xl, xl);
+    RC_TRY(cg_smooth(c, l, xl, bl, steps));
+  }
+  // V-cycles in correction form: the residual r = P (b - A x) with the operator in precision op,
+  // a V-cycle (the levels' own operators) from zero for A e = r, x += e; so the cycles converge in
+  // that precision even when the levels' products are FP32
+  int cycles = 0;
+  double res = 1.0;
+  double *r = c->r, *e = c->z;
+  for (;;) {
+    RC_TRY(apply_A(c, c->curve, x, c->tmp, op));
+    vec_copy(b0, r, n3, s);
+    vec_axpby(-1.0, c->tmp, 1.0, r, n3, s);
+    cons_project(c, c->curve, c->cons, r, r);
+    vec_dot(r, r, n3, c->red, c->scal, s);
+    double rr;
+    RC_TRY(fetch(c, c->scal, &rr, 1));
+    res = std::sqrt(rr) / bn;
+    if (trace_on()) fprintf(stderr, "[rc fmg] cycle %d res %.3e\n", cycles, res);
+    if (!(res >= o.tol) || cycles >= o.max_iter) break;
+    hipLaunchKernelGGL(k_fill, dim3(cdiv(n3, 256)), dim3(256), 0, s, e, n3, 0.0);
+    RC_TRY(vcycle_cg(c, 0, r, e, steps));
+    vec_axpby(1.0, e, 1.0, x, n3, s);
+    ++cycles;
+  }
+  *iters_out = cycles;
+  *res_out = res;
+  if (!(res < o.tol)) {
+    set_error("standalone multigrid did not reach the tolerance");
+    return RC_ERR_NOT_CONVERGED;
+  }
+  return RC_OK;
+}
+
+// The solve of the projected system for the prepared solver kind.
+static rc_status solve_projected(rc_ctx* c, const double* b, double* x, const rc_solve_opts& o, int* iters,
+                                 double* res) {
+  if (o.solver == RC_SOLVE_MG_FMG) return fmg_solve(c, b, x, o, iters, res);
+  return pcg_solve(c, b, x, o, iters, res);
+}
+
 rc_status solve_prepared(rc_ctx* c, const double* rhs, double* out, const rc_solve_opts& o, int* iters,
                          double* res) {
   if (o.solver == RC_SOLVE_DENSE) {
@@ -1236,7 +1419,7 @@ rc_status solve_prepared(rc_ctx* c, const double* rhs, double* out, const rc_sol
     *res = 0.0;
     return sync(c);
   }
-  return pcg_solve(c, rhs, out, o, iters, res);
+  return solve_projected(c, rhs, out, o, iters, res);
 }
 
 // Projection increment for the violation phi (external order): eq.
@@ -1256,7 +1439,7 @@ static rc_status projection_increment(rc_ctx* c, const double* phi, double* x, c
   if (o.lowp_outer == 2 && c->lowp_levels > 0) RC_TRY(launch_lowp_apply(c->lowp, c->zmin, c->inc, s, nullptr));
   else RC_TRY(apply_A(c, c->curve, c->zmin, c->inc, o.op_f64 ? RC_F64 : c->dtype));
   double res = 0.0;
-  rc_status st = pcg_solve(c, c->inc, c->x, o, iters, &res);
+  rc_status st = solve_projected(c, c->inc, c->x, o, iters, &res);
   if (st != RC_OK && st != RC_ERR_NOT_CONVERGED) return st;
   vec_copy(c->zmin, x, n3, s);
   vec_axpby(-1.0, c->x, 1.0, x, n3, s);
