@@ -270,6 +270,28 @@ __device__ __forceinline__ double vertex_u(const V4<double>* __restrict__ GA, co
 
 // Per vertex: sums the chunks (fixed order) and writes
 // vout[v] = (E_v, direct gradient (3), dE/du_0 (3), dE/du_1 (3), dE/dLambda_v, 0).
+// The per-chunk partial sums of every slot, added in chunk order into chunk 0
+// (a thread per (slot, vertex), eight loads in flight), so that the finalize
+// reads one chunk: the same sums in the same order as a serial pass.
+__global__ void k_vp_reduce(double* __restrict__ part, int nchunk, int NS, int nV) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NS * nV) return;
+  const int k = i / nV, v = i % nV;
+  const size_t stride = (size_t)NS * nV;
+  const double* p = part + (size_t)k * nV + v;
+  double a = 0.0;
+  int c = 0;
+  for (; c + 8 <= nchunk; c += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = p[(size_t)(c + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a += t[u];
+  }
+  for (; c < nchunk; ++c) a += p[(size_t)c * stride];
+  part[(size_t)k * nV + v] = a;
+}
+
 __global__ void k_vp_finalize(const double* __restrict__ part, int nchunk, int nV, int grad, double beta,
                               const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GT,
                               const int* __restrict__ inc_off, const int* __restrict__ inc,
@@ -399,7 +421,13 @@ rc_status launch_tpe_vp_pairs(const Curve& c, double beta, bool grad, hipStream_
 }
 
 rc_status launch_tpe_vp_finish(const Curve& c, double beta, bool grad, double* dE, hipStream_t s) {
-  hipLaunchKernelGGL(k_vp_finalize, dim3(vp_cdiv(c.nV, 256)), dim3(256), 0, s, (const double*)c.vpart, c.vchunk, c.nV,
+  const int NS = grad ? kVpSlots : 1;
+  int nch = c.vchunk;
+  if (nch > 1) {
+    hipLaunchKernelGGL(k_vp_reduce, dim3(vp_cdiv(NS * c.nV, 256)), dim3(256), 0, s, c.vpart, nch, NS, c.nV);
+    nch = 1;
+  }
+  hipLaunchKernelGGL(k_vp_finalize, dim3(vp_cdiv(c.nV, 256)), dim3(256), 0, s, (const double*)c.vpart, nch, c.nV,
                      grad ? 1 : 0, beta, (const V4<double>*)c.gd.a, (const V4<double>*)c.gd.t,
                      (const int*)c.inc_off, (const int*)c.inc, c.vout, c.status);
   hipLaunchKernelGGL(k_vp_edge, dim3(vp_cdiv(c.nE, 256)), dim3(256), 0, s, (const double*)c.vout,
