@@ -12,13 +12,17 @@ Definitions (paper Sec. 7.1 "Constraints and Potentials"):
 * Total length: ``Phi_L = L0 - sum_I l_I`` (1 row).
 * Edge length: ``Phi_I = l0_I - l_I`` (one row per edge) with Jacobian
   ``+T_I`` at i1 and ``-T_I`` at i2.
+* Point: ``Phi_{point,i} = gamma_i - x_i`` (3 rows per pinned vertex i, in
+  the order the vertices are given), whose Jacobian is the identity block at
+  vertex i and zero elsewhere.
 * Loop length: the total-length constraint applied to every connected
   component (closed loop) separately, ``Phi_q = L0_q - sum_{I in q} l_I``
   (one row per component, components ordered by their smallest vertex), as a
   packing of several curves keeps each curve's length.
 
-Rows are stacked in the order barycenter, total length, edge lengths, loop
-lengths.
+Rows are stacked in the order barycenter, total length, points, edge lengths,
+loop lengths.  Points are passed as ``points=(vertices, targets)`` beside the
+flags (no flag of their own: an empty vertex list is no point constraint).
 Vectors in R^{3|V|} are vertex-major: entry ``3 v + c`` is coordinate c of
 vertex v.
 """
@@ -74,9 +78,10 @@ def loop_lengths(gamma, edges):
     return np.bincount(comp, weights=ell)
 
 
-def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True, Lq=None):
+def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True, Lq=None, points=None):
     """(Phi, C) for the constraint set ``mask`` (bitwise OR of the flags);
-    ``Lq`` are the loop-length targets."""
+    ``Lq`` are the loop-length targets, ``points`` = (vertices, targets [m][3])
+    the pinned vertices."""
     g = np.asarray(gamma, dtype=np.float64)
     e = np.asarray(edges)
     nV, nE = len(g), len(e)
@@ -99,6 +104,15 @@ def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True, Lq=No
                 Cl[0, 3 * e[I, 0]:3 * e[I, 0] + 3] += T[I]
                 Cl[0, 3 * e[I, 1]:3 * e[I, 1] + 3] -= T[I]
             jacs.append(Cl)
+    if points is not None and len(points[0]):
+        pv = np.asarray(points[0], dtype=np.int64)
+        px = np.asarray(points[1], dtype=np.float64).reshape(len(pv), 3)
+        phis.append((g[pv] - px).ravel())
+        if jacobian:
+            Cp = np.zeros((3 * len(pv), 3 * nV))
+            for j, v in enumerate(pv):
+                Cp[3 * j:3 * j + 3, 3 * v:3 * v + 3] = np.eye(3)
+            jacs.append(Cp)
     if mask & EDGE_LENGTH:
         phis.append(l0 - ell)
         if jacobian:
@@ -124,10 +138,10 @@ def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True, Lq=No
     return phi, C
 
 
-def jacobian_sparse(gamma, edges, mask, x0=None):
-    """The Jacobian C of ``evaluate`` for BARYCENTER, TOTAL_LENGTH and EDGE_LENGTH as a
-    scipy.sparse CSR matrix, entry by entry from the same formulas (for curves too
-    large for the dense k x 3|V| array)."""
+def jacobian_sparse(gamma, edges, mask, x0=None, points=None):
+    """The Jacobian C of ``evaluate`` for BARYCENTER, TOTAL_LENGTH, points and
+    EDGE_LENGTH as a scipy.sparse CSR matrix, entry by entry from the same
+    formulas (for curves too large for the dense k x 3|V| array)."""
     import scipy.sparse as sp
 
     g = np.asarray(gamma, dtype=np.float64)
@@ -153,6 +167,13 @@ def jacobian_sparse(gamma, edges, mask, x0=None):
                 cols.append(3 * e[:, a] + c)
                 vals.append(sgn * T[:, c])
         k += 1
+    if points is not None and len(points[0]):
+        pv = np.asarray(points[0], dtype=np.int64)
+        m = 3 * len(pv)
+        rows.append(k + np.arange(m))
+        cols.append((3 * pv[:, None] + np.arange(3)[None, :]).ravel())
+        vals.append(np.ones(m))
+        k += m
     if mask & EDGE_LENGTH:
         I = np.arange(nE)
         for a, sgn in ((0, 1.0), (1, -1.0)):
@@ -163,6 +184,6 @@ def jacobian_sparse(gamma, edges, mask, x0=None):
         k += nE
     if not rows:
         return sp.csr_matrix((0, 3 * nV))
-    vals = [np.broadcast_to(v, (nE,)) for v in vals]
+    vals = [np.broadcast_to(v, r.shape) for v, r in zip(vals, rows)]
     return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                          shape=(k, 3 * nV)).tocsr()

@@ -11,6 +11,9 @@
   transformed solve of eq. SaddleSolutionTransformation.
 * A step restores the constraints, satisfies the Armijo condition and lowers
   the energy.
+* Point constraints: the saddle solve with pins alone equals the elimination
+  onto the free vertices; one projection increment reaches moved pins exactly
+  and moves the free vertices by the A-harmonic extension.
 """
 
 import numpy as np
@@ -182,3 +185,76 @@ def test_difference_form_product():
     g, e, refs, E, dE, A, phi, C = setup(n=50)
     u = np.random.default_rng(4).normal(size=(50, 3))
     assert np.allclose(solve.apply_difference_form(A, u, block=7), A @ u, rtol=1e-12, atol=1e-12 * np.abs(A @ u).max())
+
+
+# --- point constraints (Sec. 7.1) -------------------------------------------
+
+
+def pinned(n=40, seed=21, npt=2, shift=0.0):
+    g, e = gen.trefoil(n, seed=seed)
+    pv = np.array([3, 25][:npt])
+    px = g[pv] + shift
+    return g, e, (pv, px)
+
+
+def test_point_rows_jacobian_order_and_sparse():
+    g, e, pts = pinned(shift=0.01)
+    refs = cons.reference_values(g, e)
+    mask = cons.BARYCENTER | cons.TOTAL_LENGTH | cons.EDGE_LENGTH
+    phi, C = cons.evaluate(g, e, mask, *refs, points=pts)
+    assert C.shape[0] == 4 + 6 + len(e)
+    # rows after barycenter and total length: gamma_i - x_i, identity Jacobian block
+    assert np.allclose(phi[4:10], -0.01)
+    h = 1e-6
+    for v, c in [(3, 0), (25, 2), (7, 1)]:
+        gp, gm = g.copy(), g.copy()
+        gp[v, c] += h
+        gm[v, c] -= h
+        fd = (cons.evaluate(gp, e, mask, *refs, jacobian=False, points=pts)[0]
+              - cons.evaluate(gm, e, mask, *refs, jacobian=False, points=pts)[0]) / (2 * h)
+        assert np.allclose(C[:, 3 * v + c], fd, rtol=1e-7, atol=1e-8)
+    assert np.abs(cons.jacobian_sparse(g, e, mask, refs[0], points=pts).toarray() - C).max() == 0.0
+
+
+def test_point_constraints_reduce_to_the_free_block():
+    """With point constraints alone the saddle system is the Dirichlet-type
+    elimination: g vanishes at the pinned vertices and Abar_FF g_F = dE_F on
+    the free ones (the pinned vertex removes the constant null space)."""
+    g, e, pts = pinned(npt=1)
+    _, dE = tpe.differential(g, e, 2.0, 4.5)
+    A = sum(sobolev.assemble(g, e, 2.0, 4.5))
+    _, C = cons.evaluate(g, e, 0, points=pts)
+    gt, _ = solve.projected_gradient(A, C, dE)
+    free = np.setdiff1d(np.arange(len(g)), pts[0])
+    assert np.abs(gt[pts[0]]).max() < 1e-12 * np.abs(gt).max()
+    gF = np.linalg.solve(A[np.ix_(free, free)], dE[free])
+    assert np.abs(gt[free] - gF).max() < 1e-10 * np.abs(gF).max()
+
+
+def test_point_projection_is_one_harmonic_step():
+    """Pinned targets moved by d: one projection increment lands exactly on
+    them (the constraint is linear), and the free vertices move by the
+    A-harmonic extension x_F = -A_FF^-1 A_FP d of the pinned moves."""
+    g, e, pts = pinned(npt=2)
+    d = np.array([[0.01, -0.02, 0.005], [-0.01, 0.0, 0.02]])
+    pts = (pts[0], pts[1] + d)
+    refs = cons.reference_values(g, e)
+    A = sum(sobolev.assemble(g, e, 2.0, 4.5))
+    _, C = cons.evaluate(g, e, 0, *refs, points=pts)
+    new, iters, ok = solve.project(g, e, A, C, 0, refs, points=pts)
+    assert ok and iters == 1
+    assert np.abs(new[pts[0]] - pts[1]).max() < 1e-14
+    P, free = pts[0], np.setdiff1d(np.arange(len(g)), pts[0])
+    xF = -np.linalg.solve(A[np.ix_(free, free)], A[np.ix_(free, P)] @ d)
+    assert np.abs((new - g)[free] - xF).max() < 1e-10 * np.abs(d).max()
+
+
+def test_point_constrained_step_keeps_pins():
+    g, e, pts = pinned(n=48, npt=2)
+    refs = cons.reference_values(g, e)
+    mask = cons.EDGE_LENGTH  # (total length with edge lengths would be a dependent row)
+    new, info = solve.step(g, e, 2.0, 4.5, mask, refs, points=pts)
+    assert info["ok"] and info["E1"] < info["E0"]
+    assert np.abs(new[pts[0]] - pts[1]).max() <= 1e-10 * refs[2].mean()
+    assert np.abs(info["g"][pts[0]]).max() < 1e-12 * np.abs(info["g"]).max()
+    assert np.abs(new - g).max() > 1e-4
