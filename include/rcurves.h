@@ -298,8 +298,28 @@ rc_status rc_assemble_dense(rc_ctx* ctx, const double* gamma, double* A);
 rc_status rc_set_constraints(rc_ctx* ctx, uint32_t mask, const double* gamma_ref,
                              const double* x0_h, double total_len0, const double* edge_len0);
 
+/* Point constraints (Sec. 7.1): Phi_{point,i} = gamma_i - x_i, 3 rows per
+ * pinned vertex i, whose Jacobian is the identity block at vertex i.
+ * vertices_h: HOST int32 [npt], distinct vertex indices; targets_h: HOST
+ * double [npt][3] the points x_i.  npt in [0, nV]; 0 removes them.  They
+ * join the set chosen by rc_set_constraints (which keeps them) in every
+ * solver, the projection and the step; the other constraints keep their
+ * targets.  The iterative solvers eliminate them (the projector onto null(C)
+ * with the pinned entries zero is F - F C^T (C F C^T)^-1 C F, F the free-vertex
+ * mask), so they add no rows to the small dense block of the projector; an
+ * edge-length row whose two ends are both pinned is then implied by the pins
+ * and is given a zero multiplier.  On a coarser multigrid level the coarse
+ * vertices a pinned vertex interpolates from are pinned (coarsening stops
+ * before a level would be more than a quarter pinned).
+ * Errors: RC_ERR_ARG (npt out of range, null pointers, a vertex out of range
+ * or given twice, a non-finite target).  Pins that leave the remaining
+ * constraints dependent (for instance every vertex pinned with the barycenter
+ * constraint) give RC_ERR_SINGULAR in the solve. */
+rc_status rc_set_point_constraints(rc_ctx* ctx, int32_t npt, const int32_t* vertices_h, const double* targets_h);
+
 /* Phi(gamma) (Sec. 7.1) in the row order barycenter (3), total length (1),
- * edge lengths (nE), restricted to the active set.  phi: device double [k]. */
+ * points (3 each, in the order given), edge lengths (nE), restricted to the
+ * active set.  phi: device double [k]. */
 rc_status rc_constraint_values(rc_ctx* ctx, const double* gamma, double* phi);
 
 /* Number of active constraint rows k. */

@@ -29,7 +29,8 @@ STATUS = {
 EXPORTED = [
     "rc_default_solve_opts", "rc_default_ls_opts", "rc_last_error", "rc_create", "rc_destroy", "rc_energy",
     "rc_differential", "rc_sobolev_apply", "rc_sobolev_apply_prec", "rc_sobolev_diag", "rc_assemble_dense",
-    "rc_set_constraints", "rc_constraint_values", "rc_constraint_count", "rc_project", "rc_sobolev_gradient",
+    "rc_set_constraints", "rc_set_point_constraints", "rc_constraint_values", "rc_constraint_count", "rc_project",
+    "rc_sobolev_gradient",
     "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_bh_last_work", "rc_midpoint_differential",
     "rc_profile_enable", "rc_profile_read", "rc_lowp_assemble", "rc_lowp_apply", "rc_set_obstacle",
     "rc_set_penalties",
@@ -111,6 +112,7 @@ def load():
         "rc_sobolev_diag": (I32, [P, P, P]),
         "rc_assemble_dense": (I32, [P, P, P]),
         "rc_set_constraints": (I32, [P, U32, P, P, D, P]),
+        "rc_set_point_constraints": (I32, [P, I32, P, P]),
         "rc_constraint_values": (I32, [P, P, P]),
         "rc_constraint_count": (I32, [P]),
         "rc_project": (I32, [P, P, P, P]),
@@ -312,6 +314,17 @@ class Context:
             x0p = C.cast(self._x0, C.c_void_p)
         _check(load().rc_set_constraints(self.h, int(mask), self._v(gamma_ref, "gamma_ref"), x0p,
                                          float(total_len0), _ptr(edge_len0, (self.nE,), self._f64, "edge_len0")))
+
+    def rc_set_point_constraints(self, vertices=(), targets=()):
+        """Pin vertices[j] to targets[j] (host sequences: ints, [m][3] floats)."""
+        v = [int(i) for i in vertices]
+        t = [float(x) for row in targets for x in row]
+        if len(t) != 3 * len(v):
+            raise ValueError("targets must hold three coordinates per vertex")
+        self._pv = (C.c_int32 * max(len(v), 1))(*v)
+        self._px = (C.c_double * max(len(t), 1))(*t)
+        _check(load().rc_set_point_constraints(self.h, len(v), C.cast(self._pv, C.c_void_p),
+                                               C.cast(self._px, C.c_void_p)))
 
     def rc_constraint_count(self):
         return int(load().rc_constraint_count(self.h))

@@ -171,6 +171,7 @@ static rc_status create_ctx(int32_t nV, int32_t nE, const int32_t* edges_h, doub
   RC_TRY(dalloc(&c->scal, 128));
   RC_TRY(dalloc(&c->red, (size_t)dot_scratch_size(128)));
   RC_TRY(dalloc(&c->phi, 2 * ((size_t)nE + 4)));
+  c->phi_cap = (size_t)nE + 4;
   RC_TRY(dalloc(&c->status_dev, 1));
   RC_HIP(hipMemsetAsync(c->status_dev, 0, sizeof(unsigned), c->stream));
   c->curve.status = c->status_dev;
@@ -345,9 +346,63 @@ rc_status rc_set_constraints(rc_ctx* c, uint32_t mask, const double* gamma_ref, 
   RC_TRY(sync(c));
   mg_free(c);  // the coarse levels carry constraints of the same kinds
   dense_free(c->dense);
-  RC_TRY(cons_alloc(c, c->curve, c->cons, mask));
+  RC_TRY(cons_alloc(c, c->curve, c->cons, mask, c->pts));
+  if (!c->pts.empty())
+    RC_HIP(hipMemcpy(c->cons.ptx, c->pts_x.data(), sizeof(double) * c->pts_x.size(), hipMemcpyHostToDevice));
   if (mask == 0) return RC_OK;
   return cons_set_targets(c, gamma_ref, x0_h, total_len0, edge_len0);
+}
+
+rc_status rc_set_point_constraints(rc_ctx* c, int32_t npt, const int32_t* vertices_h, const double* targets_h) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_set_point_constraints"));
+  if (npt < 0 || npt > c->nV || (npt > 0 && (!vertices_h || !targets_h))) {
+    set_error("point constraints: npt must lie in [0, nV], with host vertices and targets when positive");
+    return RC_ERR_ARG;
+  }
+  std::vector<int> pts(vertices_h, vertices_h + npt);
+  std::vector<double> px(targets_h, targets_h + 3 * (size_t)npt);
+  std::vector<int> sorted = pts;
+  std::sort(sorted.begin(), sorted.end());
+  if (npt > 0 && (sorted.front() < 0 || sorted.back() >= c->nV ||
+                  std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())) {
+    set_error("point constraints: vertex out of range or given twice");
+    return RC_ERR_ARG;
+  }
+  for (double v : px)
+    if (!std::isfinite(v)) {
+      set_error("point constraints: non-finite target");
+      return RC_ERR_ARG;
+    }
+  RC_TRY(sync(c));
+  // Phi and its negation in the projection (2 k values)
+  const size_t kmax = (size_t)c->nE + 4 + 3 * (size_t)npt;
+  if (kmax > c->phi_cap) {
+    hipFree(c->phi);
+    RC_TRY(dalloc(&c->phi, 2 * kmax));
+    c->phi_cap = kmax;
+  }
+  // re-lay the finest level's rows, keeping the other constraints' targets
+  Cons& k = c->cons;
+  const uint32_t mask = k.mask;
+  const double total0 = k.total0;
+  double x0[3] = {0.0, 0.0, 0.0};
+  std::vector<double> len0;
+  if (k.geo) {
+    RC_TRY(fetch(c, k.x0, x0, 3));
+    len0.resize(c->nE);
+    RC_TRY(fetch(c, k.len0, len0.data(), c->nE));
+  }
+  mg_free(c);
+  dense_free(c->dense);
+  c->pts = pts;
+  c->pts_x = px;
+  RC_TRY(cons_alloc(c, c->curve, k, mask, c->pts));
+  k.total0 = total0;
+  RC_HIP(hipMemcpy(k.x0, x0, sizeof(double) * 3, hipMemcpyHostToDevice));
+  if (!len0.empty()) RC_HIP(hipMemcpy(k.len0, len0.data(), sizeof(double) * c->nE, hipMemcpyHostToDevice));
+  if (npt) RC_HIP(hipMemcpy(k.ptx, px.data(), sizeof(double) * px.size(), hipMemcpyHostToDevice));
+  return RC_OK;
 }
 
 int32_t rc_constraint_count(const rc_ctx* c) { return c ? c->cons.k : 0; }

@@ -48,6 +48,10 @@ void cons_phi_edge(const double* geo, const double* x0, int nE, const double* le
 void cons_border_rows(const double* geo, const int* inc_off, const int* inc, const int2* edges, const double* x0,
                       int nV, int bary, int total, const int* cut_edge, int ncut, double* rows, int nrows,
                       hipStream_t s);
+// point constraints by elimination: weights (w or 1) times the free mask, masking, unit zero diagonals
+void free_weights(const double* w, const double* free, int nV, double* out, hipStream_t s);
+void mask_vertices(double* x, const double* free, int nV, hipStream_t s);
+void unit_zero_diag(double* A, int n, hipStream_t s);
 void cons_path_coeffs(const double* geo, const int2* edges, const int* path_edge, const int* path_prev, int np,
                       const double* w, double* ta, double* td, double* tc, hipStream_t s);
 void cons_scale_rows(const double* rows, const double* w, int nV, int nrows, double* out, hipStream_t s);
@@ -114,6 +118,8 @@ void cons_project_pack(const double* geo, const int2* edges, const int* path_edg
 
 // dense direct path
 void dense_build_H(const double* A, const double* CtC, int nV, double* H, hipStream_t s);
-void dense_C_edges(const double* geo, const int2* edges, int nE, int row0, int nV, double* Cd, hipStream_t s);
+void dense_C_edges(const double* geo, const int2* edges, int nE, int row0, int nV, const double* free, double* Cd,
+                   hipStream_t s);
+void dense_C_points(const int* pt, int npt, int row0, int nV, double* Cd, hipStream_t s);
 
 }  // namespace rc

@@ -578,7 +578,8 @@ void cons_phi_edge(const double* geo, const double* x0, int nE, const double* le
   hipLaunchKernelGGL(k_cons_phi_edge, dim3(cdiv(nE, 256)), dim3(256), 0, s, geo, x0, nE, len0, vals, phi_edges);
 }
 
-// Border rows as dense vertex vectors rows[r][nV][3].
+// Border rows as dense vertex vectors rows[r][nV][3], in the order barycenter (3),
+// total length (1), cut edges (1 each).
 //   barycenter row c: at v, sum_{I at v} (l_I/2) e_c + sigma_I(v) (x_I - x0)_c T_I, sigma(i1) = -1, sigma(i2) = +1
 //   total-length row: at v, sum_{I at v} s_I(v) T_I with s(i1) = +1, s(i2) = -1
 //   cut-edge row for edge I: +T_I at i1, -T_I at i2
@@ -649,6 +650,9 @@ __global__ void k_path_coeffs(const double* __restrict__ geo, const int2* __rest
   const int I = path_edge[k];
   const int2 ei = edges[I];
   td[k] = w ? w[ei.x] + w[ei.y] : 2.0;
+  // both ends of zero weight (pinned vertices): the row of C W C^T is zero and its constraint
+  // holds for every admissible vector; a unit diagonal gives it a zero multiplier (pseudo-inverse)
+  if (td[k] == 0.0) td[k] = 1.0;
   if (path_prev[k]) {
     const int J = path_edge[k - 1];
     const int2 ej = edges[J];
@@ -1322,14 +1326,17 @@ void dense_build_H(const double* A, const double* CtC, int nV, double* H, hipStr
   hipLaunchKernelGGL(k_build_H, g, b, 0, s, A, CtC, nV, H);
 }
 
-// Dense constraint matrix in the external row order (bary, total, edges) from
-// the border rows and the edge rows: Cd[k][3 nV].
+// Dense constraint matrix in the external row order (bary, total, points, edges)
+// from the border rows, the point rows and the edge rows: Cd[k][3 nV].  An
+// edge whose ends are both pinned (free[v] = 0) keeps a zero row: its
+// linearised length is fixed by the point rows, so the row would be dependent.
 __global__ void k_dense_C_edges(const double* __restrict__ geo, const int2* __restrict__ edges, int nE, int row0,
-                                int nV, double* __restrict__ Cd) {
+                                int nV, const double* __restrict__ free, double* __restrict__ Cd) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nE) return;
   const double* g = geo + 8 * (size_t)I;
   int2 e = edges[I];
+  if (free && free[e.x] == 0.0 && free[e.y] == 0.0) return;
   double* r = Cd + (size_t)(row0 + I) * 3 * nV;
   for (int cc = 0; cc < 3; ++cc) {
     r[3 * e.x + cc] = g[1 + cc];
@@ -1337,8 +1344,51 @@ __global__ void k_dense_C_edges(const double* __restrict__ geo, const int2* __re
   }
 }
 
-void dense_C_edges(const double* geo, const int2* edges, int nE, int row0, int nV, double* Cd, hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_C_edges, dim3(cdiv(nE, 256)), dim3(256), 0, s, geo, edges, nE, row0, nV, Cd);
+void dense_C_edges(const double* geo, const int2* edges, int nE, int row0, int nV, const double* free, double* Cd,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_C_edges, dim3(cdiv(nE, 256)), dim3(256), 0, s, geo, edges, nE, row0, nV, free, Cd);
+}
+
+// point rows (Sec. 7.1, Phi = gamma_i - x_i): row row0 + 3 j + c of Cd is e_c at vertex pt[j]
+__global__ void k_dense_C_points(const int* __restrict__ pt, int npt, int row0, int nV, double* __restrict__ Cd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * npt) return;
+  Cd[(size_t)(row0 + i) * 3 * nV + 3 * pt[i / 3] + i % 3] = 1.0;
+}
+
+void dense_C_points(const int* pt, int npt, int row0, int nV, double* Cd, hipStream_t s) {
+  if (npt > 0) hipLaunchKernelGGL(k_dense_C_points, dim3(cdiv(3 * npt, 64)), dim3(64), 0, s, pt, npt, row0, nV, Cd);
+}
+
+// A[i][i] = 1 where the diagonal of the SPD matrix A [n][n] is exactly zero (a zero row and column)
+__global__ void k_unit_zero_diag(double* __restrict__ A, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && A[(size_t)i * n + i] == 0.0) A[(size_t)i * n + i] = 1.0;
+}
+
+void unit_zero_diag(double* A, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_unit_zero_diag, dim3(cdiv(n, 256)), dim3(256), 0, s, A, n);
+}
+
+// out[v] = (w ? w[v] : 1) free[v]: the weights of C W C^T with the pinned vertices' columns removed
+__global__ void k_free_weights(const double* __restrict__ w, const double* __restrict__ free, int nV,
+                               double* __restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < nV) out[v] = (w ? w[v] : 1.0) * free[v];
+}
+
+void free_weights(const double* w, const double* free, int nV, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_free_weights, dim3(cdiv(nV, 256)), dim3(256), 0, s, w, free, nV, out);
+}
+
+// x[v] *= free[v] (3 components)
+__global__ void k_mask_vertices(double* __restrict__ x, const double* __restrict__ free, int nV) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 3 * nV) x[i] *= free[i / 3];
+}
+
+void mask_vertices(double* x, const double* free, int nV, hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_vertices, dim3(cdiv(3 * nV, 256)), dim3(256), 0, s, x, free, nV);
 }
 
 }  // namespace rc

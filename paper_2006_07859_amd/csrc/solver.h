@@ -19,7 +19,17 @@ struct Cons {
   uint32_t mask = 0;
   int bary = 0, total = 0, edge = 0;
   int nb = 0, np = 0, ncut = 0, k = 0;  // border rows, path rows, cut edges, all rows
+  // point constraints (Sec. 7.1) are eliminated rather than bordered: with F = diag(free),
+  // free[v] = 0 at the pinned vertices, the projector onto null(C) n {x_P = 0} is
+  // F - F C^T (C F C^T)^-1 C F, the weighted projector with W = F (and the smoother's
+  // W = D^-1 F), so they add no border rows
+  int npt = 0, nbt = 0, nd = 0;         // pinned vertices; barycenter + total rows; rows before the edge rows
   double total0 = 0.0;
+  std::vector<int> h_pt;                // pinned vertices, in row order
+  int* pt = nullptr;
+  double* ptx = nullptr;                // their targets x_i [npt][3]
+  double* free = nullptr;               // [nV] 0 at pinned vertices, else 1 (npt > 0)
+  double* weff = nullptr;               // [nV] the weights of the prepared factors (w or 1) * free
   std::vector<int> h_path_edge, h_path_prev, h_cut_edge, h_edge_path_row;
   int *path_edge = nullptr, *path_prev = nullptr, *cut_edge = nullptr, *edge_path_row = nullptr;
   double *x0 = nullptr, *len0 = nullptr, *ones = nullptr;
@@ -172,6 +182,10 @@ struct rc_ctx {
   float *learn_X = nullptr, *learn_Y = nullptr;
   bool mg_learned = false;  // the V-cycle's smoothers take the attached MLP's weights
   bool mg_cg = false;       // the standalone multigrid with CG smoothing (no Chebyshev interval)
+  // point constraints of the finest level (kept across rc_set_constraints)
+  std::vector<int> pts;
+  std::vector<double> pts_x;
+  size_t phi_cap = 0;  // rows the phi buffer holds (twice)
 };
 
 struct rc_mlp {
@@ -184,7 +198,7 @@ rc_status sync(rc_ctx* c);
 rc_status fetch(rc_ctx* c, const double* dev, double* host, int n);
 bool trace_on();
 
-rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask);
+rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const std::vector<int>& pts = {});
 void cons_free(Cons& k);
 rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma, const double* w = nullptr);
 // With pop, the last launch also writes the operand of pop's next product,

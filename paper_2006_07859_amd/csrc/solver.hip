@@ -92,14 +92,50 @@ static bool invert_small(std::vector<double>& A, int n) {
 // ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
-__global__ void k_map_rhs(const double* __restrict__ b, int bary, int total, const int* __restrict__ path_edge,
-                          int np, const int* __restrict__ cut_edge, int ncut, double* __restrict__ wp,
+// b in external order (barycenter and total length [nbt], points, edges from nd) -> path rows wp
+// and border rows wb (barycenter, total length, cut edges)
+__global__ void k_map_rhs(const double* __restrict__ b, int nbt, int nd, const int* __restrict__ path_edge, int np,
+                          const int* __restrict__ cut_edge, int ncut, double* __restrict__ wp,
                           double* __restrict__ wb, double sign) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nd = 3 * bary + total;
   if (i < np) wp[i] = sign * b[nd + path_edge[i]];
-  if (i < nd) wb[i] = sign * b[i];
-  if (i < ncut) wb[nd + i] = sign * b[nd + cut_edge[i]];
+  if (i < nbt) wb[i] = sign * b[i];
+  if (i < ncut) wb[nbt + i] = sign * b[nd + cut_edge[i]];
+}
+
+// With pinned vertices a particular solution of C z = b sets z_P = b_P (the point rows of b)
+// and solves the other rows for the free part: their right-hand side loses C v_P, v_P the
+// point rows placed at their vertices (wp, wb carry the factor sign).  One thread: pins on
+// a shared row are summed in order.
+__global__ void k_pin_rhs(const double* __restrict__ b, int nbt, const int* __restrict__ pt, int npt,
+                          const double* __restrict__ rows, int nb, int nV, const double* __restrict__ geo,
+                          const int* __restrict__ inc_off, const int* __restrict__ inc,
+                          const int* __restrict__ edge_path_row, double* __restrict__ wp, double* __restrict__ wb,
+                          double sign) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int j = 0; j < npt; ++j) {
+    const int p = pt[j];
+    const double v0 = b[nbt + 3 * j], v1 = b[nbt + 3 * j + 1], v2 = b[nbt + 3 * j + 2];
+    for (int r = 0; r < nb; ++r) {
+      const double* rv = rows + ((size_t)r * nV + p) * 3;
+      wb[r] -= sign * (rv[0] * v0 + rv[1] * v1 + rv[2] * v2);
+    }
+    for (int q = inc_off[p]; q < inc_off[p + 1]; ++q) {
+      const int I = inc[q] >> 1;
+      const int pr = edge_path_row[I];
+      if (pr < 0) continue;
+      const double sg = (inc[q] & 1) ? -1.0 : 1.0;  // the edge row: +T_I at i1, -T_I at i2
+      const double* g = geo + 8 * (size_t)I;
+      wp[pr] -= sign * sg * (g[1] * v0 + g[2] * v1 + g[3] * v2);
+    }
+  }
+}
+
+// z_P = b_P (after z = F z)
+__global__ void k_pin_set(const double* __restrict__ b, int nbt, const int* __restrict__ pt, int npt,
+                          double* __restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 3 * npt) z[3 * (size_t)pt[i / 3] + i % 3] = b[nbt + i];
 }
 
 __global__ void k_phi_border(const double* __restrict__ sm, int bary, int total, double total0,
@@ -112,6 +148,14 @@ __global__ void k_phi_border(const double* __restrict__ sm, int bary, int total,
     o = 3;
   }
   if (total) phi[o] = total0 - sm[3];
+}
+
+// point rows of Phi (Sec. 7.1): gamma_i - x_i, three per pinned vertex from row0
+__global__ void k_phi_points(const double* __restrict__ gamma, const int* __restrict__ pt,
+                             const double* __restrict__ ptx, int npt, int row0, double* __restrict__ phi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * npt) return;
+  phi[row0 + i] = gamma[3 * (size_t)pt[i / 3] + i % 3] - ptx[i];
 }
 
 __global__ void k_gather_coarse(const double* __restrict__ fine, const int* __restrict__ fine_of, int nc,
@@ -189,12 +233,12 @@ __global__ void k_fill_pattern(double* __restrict__ x, int n, unsigned seed) {
 // constraints of one level
 // ---------------------------------------------------------------------------
 void cons_free(Cons& k) {
-  int* ip[] = {k.path_edge, k.path_prev, k.cut_edge, k.edge_path_row};
+  int* ip[] = {k.path_edge, k.path_prev, k.cut_edge, k.edge_path_row, k.pt};
   for (int* p : ip)
     if (p) hipFree(p);
   double* dp[] = {k.x0, k.len0, k.ones, k.geo, k.geo_eval, k.vals, k.rows, k.ta, k.td, k.tc, k.Kpb, k.Z, k.Sinv,
                   k.tri_scratch, k.wp, k.yp, k.wb, k.yb, k.dots, k.rhs, k.small, k.part, k.sp_VW, k.sp_Rt, k.sp_g,
-                  k.sp_U, k.sp_tmp};
+                  k.sp_U, k.sp_tmp, k.ptx, k.free, k.weff};
   for (double* p : dp)
     if (p) hipFree(p);
   if (k.prow) hipFree(k.prow);
@@ -203,10 +247,12 @@ void cons_free(Cons& k) {
   k = Cons();
 }
 
-rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask) {
+rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const std::vector<int>& pts) {
   (void)c;
   cons_free(k);
   k.mask = mask;
+  k.h_pt = pts;
+  k.npt = (int)pts.size();
   k.bary = (mask & RC_C_BARYCENTER) ? 1 : 0;
   k.total = (mask & RC_C_TOTAL_LENGTH) ? 1 : 0;
   k.edge = (mask & RC_C_EDGE_LENGTH) ? 1 : 0;
@@ -229,11 +275,24 @@ rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask) {
   }
   k.np = (int)k.h_path_edge.size();
   k.ncut = (int)k.h_cut_edge.size();
-  k.nb = 3 * k.bary + k.total + k.ncut;
-  k.k = 3 * k.bary + k.total + (k.edge ? nE : 0);
+  k.nbt = 3 * k.bary + k.total;
+  k.nd = k.nbt + 3 * k.npt;
+  k.nb = k.nbt + k.ncut;
+  k.k = k.nd + (k.edge ? nE : 0);
   if (k.nb > 120) {
     set_error("too many loops for edge-length constraints (at most 120 border rows)");
     return RC_ERR_UNSUPPORTED;
+  }
+  if (k.npt) {
+    RC_TRY(dalloc(&k.pt, k.npt));
+    RC_TRY(dalloc(&k.ptx, 3 * (size_t)k.npt));
+    RC_TRY(dalloc(&k.free, nV));
+    RC_TRY(dalloc(&k.weff, nV));
+    std::vector<double> fr(nV, 1.0);
+    for (int v : pts) fr[v] = 0.0;
+    RC_HIP(hipMemcpy(k.pt, pts.data(), sizeof(int) * k.npt, hipMemcpyHostToDevice));
+    RC_HIP(hipMemset(k.ptx, 0, sizeof(double) * 3 * k.npt));
+    RC_HIP(hipMemcpy(k.free, fr.data(), sizeof(double) * nV, hipMemcpyHostToDevice));
   }
   RC_TRY(dalloc(&k.path_edge, k.np));
   RC_TRY(dalloc(&k.path_prev, k.np));
@@ -325,11 +384,16 @@ static TriSys path_sys(const Cons& k) {
 }
 
 // C(gamma), the tridiagonal path block and the border Schur complement, of
-// C C^T, or of C W C^T with W = diag(w) per vertex when w is given.
+// C C^T, or of C W C^T with W = diag(w) per vertex when w is given (times the
+// free mask when vertices are pinned).
 rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma, const double* w) {
   if (k.k == 0) return RC_OK;
   hipStream_t s = c->stream;
   const int nV = cv.nV, nE = cv.nE;
+  if (k.npt) {
+    free_weights(w, k.free, nV, k.weff, s);
+    w = k.weff;
+  }
   cons_geometry(gamma, cv.edges, nE, k.geo, s);
   cons_border_rows(k.geo, cv.inc_off, cv.inc, cv.edges, k.x0, nV, k.bary, k.total, k.cut_edge, k.ncut, k.rows,
                    k.nb, s);
@@ -368,6 +432,11 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma,
     RC_TRY(fetch(c, k.dots, S.data(), nb * nb));
     if (np > 0) RC_TRY(fetch(c, k.small, kz.data(), nb * nb));
     for (int i = 0; i < nb * nb; ++i) S[i] -= kz[i];
+    // a border row that vanishes on the free vertices (a cut edge with both ends pinned) is zero
+    // in S: a unit diagonal gives it a zero multiplier
+    if (k.npt)
+      for (int i = 0; i < nb; ++i)
+        if (S[i * nb + i] == 0.0) S[i * nb + i] = 1.0;
     if (!invert_small(S, nb)) {
       set_error("constraint Schur complement is singular (dependent constraints?)");
       return RC_ERR_SINGULAR;
@@ -438,7 +507,7 @@ static void cons_project_w(rc_ctx* c, const Curve& cv, Cons& kw, const double* w
                            bool xset = false, const LowpOp* pop = nullptr, bool pfrom_x = false) {
   ProjData d = proj_data(cv, kw);
   set_prep(d, pop, pfrom_x);
-  d.w = w;
+  d.w = kw.npt ? kw.weff : w;  // (w times the free mask with pinned vertices, as prepared)
   d.scale = scale;
   d.beta = beta;
   d.prev = prev;
@@ -447,8 +516,10 @@ static void cons_project_w(rc_ctx* c, const Curve& cv, Cons& kw, const double* w
   cons_project_fused(d, in, out, c->stream);
 }
 
-// out = P in with P = I - C^T (C C^T)^-1 C (in may equal out); with xacc, also
-// xacc += out.
+// out = P in with P = I - C^T (C C^T)^-1 C (in may equal out), the orthogonal
+// projector onto null(C); with pinned vertices P = F - F C^T (C F C^T)^-1 C F
+// (F the free mask), onto null(C) with the pinned entries zero.  With xacc,
+// also xacc += out.
 bool cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double* out, double* xacc,
                   const LowpOp* pop, bool pfrom_x) {
   hipStream_t s = c->stream;
@@ -460,43 +531,64 @@ bool cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double*
   }
   if (k.nb <= kProjMaxBorder) {
     ProjData d = proj_data(cv, k);
+    d.w = k.npt ? k.weff : nullptr;
     d.xacc = xacc;
     set_prep(d, pop, pfrom_x);
     cons_project_fused(d, in, out, s);
     return pop != nullptr;
   }
+  if (k.npt) {  // F in, then F (F in - C^T y) with y from C F in
+    if (in != out) vec_copy(in, out, 3 * nV, s);
+    mask_vertices(out, k.free, nV, s);
+    in = out;
+  }
   cons_path_apply(k.geo, cv.edges, k.path_edge, k.np, in, nV, 1, k.wp, s);
   if (k.nb > 0) vec_dots(k.rows, 3 * nV, in, 0, 3 * nV, k.nb, c->red, k.wb, s);
   cons_solve_K(c, k);
   cons_apply_CT(k.geo, cv.inc_off, cv.inc, k.edge_path_row, k.yp, k.rows, k.yb, k.nb, nV, in, out, s);
+  if (k.npt) mask_vertices(out, k.free, nV, s);
   if (xacc) vec_axpby(1.0, out, 1.0, xacc, 3 * nV, s);
   return false;
 }
 
-// z = C^T (C C^T)^-1 b for an external-order b (finest level).
+// A particular solution z of C z = b for an external-order b (finest level):
+// z = C^T (C C^T)^-1 b, the minimum-norm one, without pinned vertices; with
+// them z_P = b_P and z_F = F C^T (C F C^T)^-1 (b_C - C v_P) (v_P the point
+// rows of b at their vertices), which satisfies every row.
 static void cons_min_norm(rc_ctx* c, const double* b, double* z) {
   Cons& k = c->cons;
+  hipStream_t s = c->stream;
+  const int nV = c->nV;
   const int n = std::max(k.np, std::max(k.nb, 1));
-  hipLaunchKernelGGL(k_map_rhs, dim3(cdiv(n, 256)), dim3(256), 0, c->stream, b, k.bary, k.total, k.path_edge, k.np,
+  hipLaunchKernelGGL(k_map_rhs, dim3(cdiv(n, 256)), dim3(256), 0, s, b, k.nbt, k.nd, k.path_edge, k.np,
                      k.cut_edge, k.ncut, k.wp, k.wb, -1.0);
+  if (k.npt)
+    hipLaunchKernelGGL(k_pin_rhs, dim3(1), dim3(1), 0, s, b, k.nbt, k.pt, k.npt, k.rows, k.nb, nV, k.geo,
+                       c->curve.inc_off, c->curve.inc, k.edge_path_row, k.wp, k.wb, -1.0);
   cons_solve_K(c, k);
   // apply_CT computes in - C^T y with in = null: -C^T y, and y = K^-1 (-b)
-  cons_apply_CT(k.geo, c->curve.inc_off, c->curve.inc, k.edge_path_row, k.yp, k.rows, k.yb, k.nb, c->nV, nullptr, z,
-                c->stream);
+  cons_apply_CT(k.geo, c->curve.inc_off, c->curve.inc, k.edge_path_row, k.yp, k.rows, k.yb, k.nb, nV, nullptr, z,
+                s);
+  if (k.npt) {
+    mask_vertices(z, k.free, nV, s);
+    hipLaunchKernelGGL(k_pin_set, dim3(cdiv(3 * k.npt, 64)), dim3(64), 0, s, b, k.nbt, k.pt, k.npt, z);
+  }
 }
 
-// Phi(gamma) in external order (barycenter, total length, edges).
+// Phi(gamma) in external order (barycenter, total length, points, edges).
 void cons_values(rc_ctx* c, const double* gamma, double* phi) {
   Cons& k = c->cons;
   hipStream_t s = c->stream;
   const int nE = c->nE;
   cons_geometry(gamma, c->curve.edges, nE, k.geo_eval, s);
-  const int nd = 3 * k.bary + k.total;
-  cons_phi_edge(k.geo_eval, k.x0, nE, k.len0, k.vals, k.edge ? phi + nd : nullptr, s);
-  if (nd > 0) {
+  const int nbt = 3 * k.bary + k.total;
+  cons_phi_edge(k.geo_eval, k.x0, nE, k.len0, k.vals, k.edge ? phi + k.nd : nullptr, s);
+  if (nbt > 0) {
     vec_dots(k.vals, nE, k.ones, 0, nE, 4, c->red, k.small, s);
     hipLaunchKernelGGL(k_phi_border, dim3(1), dim3(1), 0, s, k.small, k.bary, k.total, k.total0, phi);
   }
+  if (k.npt > 0)
+    hipLaunchKernelGGL(k_phi_points, dim3(cdiv(3 * k.npt, 64)), dim3(64), 0, s, gamma, k.pt, k.ptx, k.npt, nbt, phi);
 }
 
 // ---------------------------------------------------------------------------
@@ -550,11 +642,13 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
   RC_TRY(launch_geometry(cv, gamma, RC_F32, s));
   RC_TRY(launch_assemble_dense(cv, c->alpha, c->beta, d.A, s));
   if (kk > 0) {
-    // dense C in external order: border rows (barycenter, total length), then edge rows
-    const int nd = 3 * k.bary + k.total;
+    // dense C in external order: the border rows of barycenter and total length, the point
+    // rows, then the edge rows
     RC_HIP(hipMemsetAsync(d.Cd, 0, sizeof(double) * (size_t)kk * n, s));
-    if (nd > 0) RC_HIP(hipMemcpyAsync(d.Cd, k.rows, sizeof(double) * (size_t)nd * n, hipMemcpyDeviceToDevice, s));
-    if (k.edge) dense_C_edges(k.geo, cv.edges, cv.nE, nd, nV, d.Cd, s);
+    if (k.nbt > 0)
+      RC_HIP(hipMemcpyAsync(d.Cd, k.rows, sizeof(double) * (size_t)k.nbt * n, hipMemcpyDeviceToDevice, s));
+    dense_C_points(k.pt, k.npt, k.nbt, nV, d.Cd, s);
+    if (k.edge) dense_C_edges(k.geo, cv.edges, cv.nE, k.nd, nV, k.free, d.Cd, s);
     dense_gemm(d.Cd, d.Cd, d.CtC, n, n, kk, 0.0, true, s);
   } else {
     // no constraint: regularise the constant null space with rho 1 1^T per component
@@ -572,6 +666,7 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
   if (kk > 0) {
     dense_gemm(d.X, d.Cd, d.W, n, kk, n, 0.0, false, s, true);  // W = H^-1 C^T
     dense_gemm(d.Cd, d.W, d.Sinv, kk, kk, n, 0.0, false, s);    // S = C H^-1 C^T (SPD)
+    if (k.npt) unit_zero_diag(d.Sinv, kk, s);  // the zero rows of edges with both ends pinned
     gj_invert_spd(d.Sinv, kk, d.gjm, d.gjo, d.gjc, d.info + 1, s);
     // X += (-W S^-1) W^T, with -W S^-1 staged in CtC (no longer needed)
     dense_gemm(d.W, d.Sinv, d.CtC, n, kk, kk, 0.0, false, s);
@@ -664,6 +759,7 @@ static rc_status mg_build(rc_ctx* c) {
   mg_free(c);
   c->levels.emplace_back(nullptr);
   const Curve* fine = &c->curve;
+  std::vector<int> fine_pts = c->cons.h_pt;
   while (fine->nV > c->mg_min) {
     std::vector<Chain> chs = chains_of(*fine);
     // black/white coarsening: keep even chain positions, and both ends of open paths
@@ -700,6 +796,11 @@ static rc_status mg_build(rc_ctx* c) {
     for (int v = 0; ok && v < fine->nV; ++v)
       if (prolong[v].x < 0) ok = false;  // isolated vertices are not coarsened
     if (!ok || fine_of.size() == (size_t)fine->nV) break;
+    std::vector<int> coarse_pts;
+    for (int v : fine_pts)
+      for (int q : {prolong[v].x, prolong[v].y})
+        if (std::find(coarse_pts.begin(), coarse_pts.end(), q) == coarse_pts.end()) coarse_pts.push_back(q);
+    if (4 * coarse_pts.size() > fine_of.size()) break;  // keep most of a level free
     auto L = std::make_unique<Level>();
     const int nc = (int)fine_of.size();
     RC_TRY(L->curve.init(nc, (int)cedges.size() / 2, cedges.data()));
@@ -722,8 +823,10 @@ static rc_status mg_build(rc_ctx* c) {
     RC_TRY(dalloc(&L->restr_idx, idx.size()));
     RC_HIP(hipMemcpy(L->restr_off, off.data(), sizeof(int) * (nc + 1), hipMemcpyHostToDevice));
     RC_HIP(hipMemcpy(L->restr_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice));
-    // the level's own constraints (same kinds as the finest level)
-    RC_TRY(cons_alloc(c, L->curve, L->cons, c->cons.mask));
+    // the level's own constraints (same kinds as the finest level); a pinned vertex pins the
+    // coarse vertices it interpolates from, so that every prolonged correction vanishes on it
+    RC_TRY(cons_alloc(c, L->curve, L->cons, c->cons.mask, coarse_pts));
+    fine_pts = coarse_pts;
     if (c->cons.bary)
       RC_HIP(hipMemcpy(L->cons.x0, c->cons.x0, sizeof(double) * 3, hipMemcpyDeviceToDevice));
     c->levels.push_back(std::move(L));
@@ -795,7 +898,8 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
   const rc_dtype prec = c->dtype;
   // the smoothers' weighted projector needs every smoothed level's border in the fused projector
   c->mg_weighted = c->cons.k > 0;
-  for (int l = 0; l < nl - 1; ++l) c->mg_weighted = c->mg_weighted && level_cons(c, l).nb <= kProjMaxBorder;
+  for (int l = 0; l < nl - 1; ++l)
+    c->mg_weighted = c->mg_weighted && level_cons(c, l).nb <= kProjMaxBorder && level_cons(c, l).k > 0;
   for (int l = 0; l < nl - 1; ++l) {
     const Curve& cv = level_curve(c, l);
     MGLevelState& st = c->mg[l];
@@ -825,7 +929,7 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
     const int n = cv.nV;
     if (c->mg_weighted) {  // factors of C W C^T, W = D^-1
       Cons& Kw = level_cons_w(c, l);
-      if (Kw.mask != K.mask || !Kw.geo) RC_TRY(cons_alloc(c, cv, Kw, K.mask));
+      if (Kw.mask != K.mask || Kw.h_pt != K.h_pt || !Kw.geo) RC_TRY(cons_alloc(c, cv, Kw, K.mask, K.h_pt));
       RC_HIP(hipMemcpyAsync(Kw.x0, K.x0, sizeof(double) * 3, hipMemcpyDeviceToDevice, s));
       hipLaunchKernelGGL(k_recip, dim3(cdiv(n, 256)), dim3(256), 0, s, st.diag, n, st.w);
       RC_TRY(cons_prepare(c, cv, Kw, l == 0 ? gamma : c->levels[l]->gamma, st.w));
@@ -1424,8 +1528,9 @@ rc_status solve_prepared(rc_ctx* c, const double* rhs, double* out, const rc_sol
 
 // Projection increment for the violation phi (external order): eq.
 // ConstraintSaddlePointProblem, through eq. SaddleSolutionTransformation on
-// the PCG paths (z = C^T (C C^T)^-1 (-phi), y from the projected system with
-// right-hand side Abar z, x = z - y).
+// the PCG paths (z with C z = -phi, y from the projected system with
+// right-hand side Abar z, x = z - y; any particular solution z gives the same
+// x, the minimum-norm one C^T (C C^T)^-1 (-phi) without pinned vertices).
 static rc_status projection_increment(rc_ctx* c, const double* phi, double* x, const rc_solve_opts& o, int* iters) {
   hipStream_t s = c->stream;
   const int n3 = 3 * c->nV, k = c->cons.k;
