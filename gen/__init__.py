@@ -14,4 +14,5 @@ from .curves import (  # noqa: F401
     packing_batch,
     round_to_f32,
     loop_edges,
+    theta_graph,
 )

@@ -22,6 +22,7 @@ __all__ = [
     "packing_instance",
     "packing_batch",
     "round_to_f32",
+    "theta_graph",
 ]
 
 
@@ -155,3 +156,29 @@ def packing_batch(n_instances: int = 512, seed: int = 0, **kw):
     """``n_instances`` independent packing instances from one seeded stream."""
     rng = np.random.default_rng(seed)
     return [packing_instance(rng, **kw) for _ in range(n_instances)]
+
+
+def theta_graph(n_arc: int = 32, n_arcs: int = 3, seed: int = 0, jitter_var: float = 1e-4):
+    """A curve network with two junctions (Sec. 7.3): ``n_arcs`` arcs of ``n_arc``
+    edges each join vertex 0 at (-1, 0, 0) to vertex 1 at (1, 0, 0).
+
+    Arc k runs through ``(-cos(pi t), r sin(pi t) cos(phi_k), r sin(pi t) sin(phi_k))``,
+    ``t`` in [0, 1], with ``phi_k = 2 pi k / n_arcs`` and ``r = 0.8``, its interior
+    vertices numbered consecutively after the two junctions; i.i.d. Gaussian jitter
+    of variance ``jitter_var`` moves the interior vertices.  Edges are oriented
+    along t.
+    """
+    rng = np.random.default_rng(seed)
+    pts = [np.array([-1.0, 0.0, 0.0]), np.array([1.0, 0.0, 0.0])]
+    edges = []
+    for k in range(n_arcs):
+        phi = 2.0 * np.pi * k / n_arcs
+        t = np.arange(1, n_arc) / n_arc
+        arc = np.stack([-np.cos(np.pi * t), 0.8 * np.sin(np.pi * t) * np.cos(phi),
+                        0.8 * np.sin(np.pi * t) * np.sin(phi)], axis=1)
+        arc = arc + rng.normal(0.0, np.sqrt(jitter_var), size=arc.shape)
+        first = len(pts)
+        pts.extend(arc)
+        ids = [0] + list(range(first, first + n_arc - 1)) + [1]
+        edges.extend([ids[q], ids[q + 1]] for q in range(n_arc))
+    return np.array(pts), np.array(edges, dtype=np.int32)

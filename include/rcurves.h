@@ -225,9 +225,11 @@ const char* rc_last_error(void);
  * alpha, beta: tangent-point exponents, alpha > 1, alpha + 2 <= beta < 2 alpha + 1
  * (Lemma FiniteTangentPointEnergy; eq. TangentPointKernel).
  * dtype: precision of the pair kernels.  stream: HIP stream for all work.
- * Multigrid, edge-length constraints and dense assembly need every vertex to
- * have degree <= 2 (loops and open paths); other graphs get RC_ERR_UNSUPPORTED
- * from those calls only. */
+ * Networks with junctions (vertices of degree >= 3, Sec. 7.3) take the pair
+ * kernels, the matrix-free operator, dense assembly, every constraint, the
+ * dense and Jacobi-PCG solvers and the step; multigrid and the assembled
+ * 16-bit operator need every vertex to have degree <= 2 (loops and open
+ * paths) and give RC_ERR_UNSUPPORTED on other graphs. */
 rc_status rc_create(int32_t n_vertices, int32_t n_edges, const int32_t* edges_h,
                     double alpha, double beta, rc_dtype dtype, rc_stream stream,
                     rc_ctx** out);
@@ -287,10 +289,14 @@ rc_status rc_sobolev_apply_prec(rc_ctx* ctx, const double* gamma, const double* 
 rc_status rc_sobolev_diag(rc_ctx* ctx, const double* gamma, double* diag);
 
 /* Dense A = B + B0 in FP64: device double [nV][nV] row-major (written).
- * Needs vertex degree <= 2. */
+ * Any graph. */
 rc_status rc_assemble_dense(rc_ctx* ctx, const double* gamma, double* A);
 
-/* Choose the constraint set (bitwise OR of RC_C_*) and its targets.
+/* Choose the constraint set (bitwise OR of RC_C_*) and its targets.  With
+ * edge-length constraints every edge at a junction (a vertex of degree >= 3)
+ * and one edge per closed loop are rows of the projector's small dense block
+ * (at most 120 such rows with the barycenter and total length, else
+ * RC_ERR_UNSUPPORTED); the other edge rows form tridiagonal paths.
  * x0_h: HOST double[3] barycenter target, or NULL = the length-weighted
  * barycenter of gamma_ref.  total_len0: target total length, or a negative
  * value = that of gamma_ref.  edge_len0: DEVICE double [nE] target lengths,

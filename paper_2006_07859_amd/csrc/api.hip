@@ -339,10 +339,6 @@ rc_status rc_set_constraints(rc_ctx* c, uint32_t mask, const double* gamma_ref, 
     set_error("gamma_ref is required");
     return RC_ERR_ARG;
   }
-  if ((mask & RC_C_EDGE_LENGTH) && !c->curve.chain) {
-    set_error("edge-length constraints need every vertex to have degree <= 2");
-    return RC_ERR_UNSUPPORTED;
-  }
   RC_TRY(sync(c));
   mg_free(c);  // the coarse levels carry constraints of the same kinds
   dense_free(c->dense);

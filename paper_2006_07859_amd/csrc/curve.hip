@@ -24,10 +24,18 @@ static rc_status dmalloc(T** p, size_t n) {
   return RC_OK;
 }
 
-// Chains of a degree <= 2 graph: vertex and edge sequences of every component.
-std::vector<Chain> chains_of(const Curve& c) {
+// Chains of a degree <= 2 graph: vertex and edge sequences of every component
+// (of the kept edges' subgraph when keep is given).
+std::vector<Chain> chains_of(const Curve& c, const std::vector<char>* keep) {
   std::vector<Chain> out;
   std::vector<char> used(c.nE, 0), seen(c.nV, 0);
+  if (keep)
+    for (int I = 0; I < c.nE; ++I) used[I] = (*keep)[I] ? 0 : 1;
+  auto kept_degree = [&](int v) {
+    int d = 0;
+    for (int k = c.h_inc_off[v]; k < c.h_inc_off[v + 1]; ++k) d += keep ? ((*keep)[c.h_inc[k] >> 1] ? 1 : 0) : 1;
+    return d;
+  };
   auto other = [&](int I, int v) { return c.h_edges[2 * I] == v ? c.h_edges[2 * I + 1] : c.h_edges[2 * I]; };
   auto next_edge = [&](int v, int prevI) {
     for (int k = c.h_inc_off[v]; k < c.h_inc_off[v + 1]; ++k) {
@@ -39,7 +47,7 @@ std::vector<Chain> chains_of(const Curve& c) {
   // open paths start at degree-1 vertices
   for (int pass = 0; pass < 2; ++pass) {
     for (int v0 = 0; v0 < c.nV; ++v0) {
-      const int deg = c.h_inc_off[v0 + 1] - c.h_inc_off[v0];
+      const int deg = kept_degree(v0);
       if (seen[v0] || deg == 0) continue;
       if (pass == 0 && deg != 1) continue;
       Chain ch;

@@ -730,7 +730,7 @@ __global__ void k_mid_finalize(const double* __restrict__ part, int nchunk, int 
 }
 
 // ---------------------------------------------------------------------------
-// dense FP64 assembly (vertex-pair gather of the increment tables), degree <= 2
+// dense FP64 assembly (vertex-pair gather of the increment tables), any graph
 // ---------------------------------------------------------------------------
 // Off-diagonal entry (v, w):
 //   sum over disjoint I at v, J at w of
@@ -1144,10 +1144,6 @@ rc_status launch_edge_sums(const Curve& c, double alpha, double beta, rc_dtype p
 }
 
 rc_status launch_assemble_dense(const Curve& c, double alpha, double beta, double* A, hipStream_t s) {
-  if (!c.chain) {
-    set_error("dense assembly needs every vertex to have degree <= 2");
-    return RC_ERR_UNSUPPORTED;
-  }
   // the operator kernel's per-edge sums Wq and P0 do not depend on the input vector
   RC_TRY(launch_edge_sums(c, alpha, beta, RC_F64, s));
   const double sigma = (beta - 1.0) / alpha - 1.0;

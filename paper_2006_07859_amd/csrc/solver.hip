@@ -259,7 +259,18 @@ rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const s
   const int nV = cv.nV, nE = cv.nE;
   k.h_edge_path_row.assign(nE, -1);
   if (k.edge) {
-    for (const Chain& ch : chains_of(cv)) {
+    // with junctions (vertices of degree >= 3) every edge at a junction is a border row; the
+    // other edges form paths and loops whose rows stay tridiagonal
+    std::vector<char> keep;
+    if (!cv.chain) {
+      keep.assign(nE, 1);
+      for (int v = 0; v < nV; ++v)
+        if (cv.h_inc_off[v + 1] - cv.h_inc_off[v] >= 3)
+          for (int q = cv.h_inc_off[v]; q < cv.h_inc_off[v + 1]; ++q) keep[cv.h_inc[q] >> 1] = 0;
+      for (int I = 0; I < nE; ++I)
+        if (!keep[I]) k.h_cut_edge.push_back(I);
+    }
+    for (const Chain& ch : chains_of(cv, cv.chain ? nullptr : &keep)) {
       const int m = (int)ch.edges.size();
       for (int q = 0; q < m; ++q) {
         if (ch.loop && q == 0) {
@@ -280,7 +291,8 @@ rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const s
   k.nb = k.nbt + k.ncut;
   k.k = k.nd + (k.edge ? nE : 0);
   if (k.nb > 120) {
-    set_error("too many loops for edge-length constraints (at most 120 border rows)");
+    set_error("too many loops and junction edges for edge-length constraints (at most 120 border rows: 3 + 1 "
+              "for barycenter and total length, 1 per loop and 1 per edge at a vertex of degree >= 3)");
     return RC_ERR_UNSUPPORTED;
   }
   if (k.npt) {

@@ -1,0 +1,121 @@
+"""GPU parity on curve networks with junctions (vertices of degree three, Sec. 7.3).
+
+A theta graph (two junctions joined by three arcs) against the oracle: the
+energy and differential (FP64 and FP32, edge-pair form), the matrix-free
+operator and its diagonal, the dense FP64 assembly, the barycenter and
+edge-length constraints (every edge at a junction is a row of the projector's
+dense block: 3 + 6 rows take the general projector, edge lengths alone the
+fused one on unpacked rows), the projected gradient from the dense and
+Jacobi-PCG solvers, and the dense step of Sec. 4.4.  Multigrid reports
+RC_ERR_UNSUPPORTED on such graphs.
+"""
+
+import numpy as np
+import pytest
+
+import gen
+from oracle import constraints as cons
+from oracle import solve, sobolev, tpe
+from tests.gpu_util import banner, dev, host, relnorm, zeros
+
+pytestmark = pytest.mark.gpu
+
+BARY, TOTAL, EDGE = 1, 2, 4
+
+
+def ctx_for(g, e, a, b, dtype):
+    from paper_2006_07859_amd import Context
+
+    return Context(len(g), e, a, b, dtype)
+
+
+@pytest.mark.parametrize("n_arc", [32, 300])
+def test_junction_energy_differential_operator(lib, n_arc):
+    from paper_2006_07859_amd import RC_F32, RC_F64
+
+    g, e = gen.theta_graph(n_arc, seed=1)
+    n = len(g)
+    banner(f"theta graph n_arc={n_arc}: energy, differential, operator")
+    E_ref, G_ref = tpe.differential(g, e, 2.0, 4.5)
+    ctx = ctx_for(g, e, 2.0, 4.5, RC_F64)
+    E, dE = zeros(1), zeros(n, 3)
+    ctx.rc_differential(dev(g), E, dE)
+    assert host(E)[0] == pytest.approx(E_ref, rel=1e-12)
+    assert relnorm(host(dE), G_ref) < 1e-10
+    A = sum(sobolev.assemble(g, e, 2.0, 4.5))
+    X = np.random.default_rng(1).normal(size=(n, 3))
+    Y = zeros(n, 3)
+    ctx.rc_sobolev_apply(dev(g), dev(X), Y, prec=RC_F64)
+    assert relnorm(host(Y), A @ X) < 1e-10
+    d = zeros(n)
+    ctx.rc_sobolev_diag(dev(g), d)
+    assert relnorm(host(d), np.diag(A)) < 1e-10
+    Ad = zeros(n, n)
+    ctx.rc_assemble_dense(dev(g), Ad)
+    assert np.abs(host(Ad) - A).max() < 1e-11 * np.abs(A).max()
+    ctx.close()
+    gf = gen.round_to_f32(g)
+    E_ref, G_ref = tpe.differential(gf, e, 2.0, 4.5)
+    ctx = ctx_for(gf, e, 2.0, 4.5, RC_F32)
+    ctx.rc_differential(dev(gf), E, dE)
+    assert host(E)[0] == pytest.approx(E_ref, rel=1e-5)
+    assert relnorm(host(dE), G_ref) < 1e-4
+    ctx.close()
+
+
+@pytest.mark.parametrize("mask", [BARY | EDGE, EDGE, BARY | TOTAL])
+def test_junction_constraints_and_projector(lib, mask):
+    from paper_2006_07859_amd import RC_F64
+
+    g, e = gen.theta_graph(40, seed=2)
+    n = len(g)
+    banner(f"theta graph constraints mask={mask}")
+    ctx = ctx_for(g, e, 2.0, 4.5, RC_F64)
+    ctx.rc_set_constraints(mask, dev(g))
+    refs = cons.reference_values(g, e)
+    gp = g + 0.01 * np.random.default_rng(0).normal(size=g.shape)
+    phi_ref, C = cons.evaluate(gp, e, mask, *refs)
+    phi = zeros(ctx.rc_constraint_count())
+    ctx.rc_constraint_values(dev(gp), phi)
+    assert np.abs(host(phi) - phi_ref).max() < 1e-12 * (np.abs(phi_ref).max() + 1)
+    X = np.random.default_rng(1).normal(size=g.shape)
+    x = X.ravel()
+    ref = x - C.T @ np.linalg.solve(C @ C.T, C @ x)
+    Y = zeros(n, 3)
+    ctx.rc_project(dev(gp), dev(X), Y)
+    assert relnorm(host(Y).ravel(), ref) < 1e-11
+    ctx.close()
+
+
+@pytest.mark.parametrize("mask", [BARY | EDGE, BARY])
+def test_junction_gradient_and_step(lib, mask):
+    from paper_2006_07859_amd import (RC_F64, RC_SOLVE_DENSE, RC_SOLVE_PCG_JACOBI, RC_SOLVE_PCG_MG, RcError,
+                                      default_solve_opts)
+
+    g, e = gen.theta_graph(40, seed=3)
+    n = len(g)
+    banner(f"theta graph projected gradient and step mask={mask}, n={n}")
+    refs = cons.reference_values(g, e)
+    _, dE = tpe.differential(g, e, 2.0, 4.5)
+    A = sum(sobolev.assemble(g, e, 2.0, 4.5))
+    _, C = cons.evaluate(g, e, mask, *refs)
+    g_ref, _ = solve.projected_gradient(A, C, dE)
+    ctx = ctx_for(g, e, 2.0, 4.5, RC_F64)
+    ctx.rc_set_constraints(mask, dev(g))
+    out = zeros(n, 3)
+    ctx.rc_sobolev_gradient(dev(g), dev(dE), out, default_solve_opts(solver=RC_SOLVE_DENSE))
+    assert relnorm(host(out), g_ref) < 1e-8
+    st = ctx.rc_sobolev_gradient(dev(g), dev(dE), out,
+                                 default_solve_opts(solver=RC_SOLVE_PCG_JACOBI, tol=1e-11, max_iter=6000))
+    assert st["residual"] < 1e-11
+    assert relnorm(host(out), g_ref) < 1e-7
+    with pytest.raises(RcError):
+        ctx.rc_sobolev_gradient(dev(g), dev(dE), out, default_solve_opts(solver=RC_SOLVE_PCG_MG))
+    new_ref, info = solve.step(g, e, 2.0, 4.5, mask, refs)
+    gam = dev(g)
+    st = ctx.rc_step(gam, so=default_solve_opts(solver=RC_SOLVE_DENSE))
+    assert st["energy"] == pytest.approx(info["E0"], rel=1e-12)
+    assert st["tau"] == info["tau"]
+    assert st["energy_new"] == pytest.approx(info["E1"], rel=1e-10)
+    assert relnorm(host(gam) - g, new_ref - g) < 1e-7
+    ctx.close()

@@ -258,3 +258,26 @@ def test_point_constrained_step_keeps_pins():
     assert np.abs(new[pts[0]] - pts[1]).max() <= 1e-10 * refs[2].mean()
     assert np.abs(info["g"][pts[0]]).max() < 1e-12 * np.abs(info["g"]).max()
     assert np.abs(new - g).max() > 1e-4
+
+
+def test_junction_graph_constraints_and_saddle():
+    """A theta graph (two vertices of degree three): the edge-length and barycenter
+    Jacobians equal central differences, and the saddle solve's two routes agree."""
+    g, e = gen.theta_graph(8, seed=2)
+    mask = cons.BARYCENTER | cons.EDGE_LENGTH
+    refs = cons.reference_values(g, e)
+    _, C = cons.evaluate(g, e, mask, *refs)
+    h = 1e-6
+    for v, c in [(0, 0), (1, 2), (5, 1)]:
+        gp, gm = g.copy(), g.copy()
+        gp[v, c] += h
+        gm[v, c] -= h
+        fd = (cons.evaluate(gp, e, mask, *refs, jacobian=False)[0]
+              - cons.evaluate(gm, e, mask, *refs, jacobian=False)[0]) / (2 * h)
+        assert np.allclose(C[:, 3 * v + c], fd, rtol=1e-7, atol=1e-8)
+    _, dE = tpe.differential(g, e, 2.0, 4.5)
+    A = sum(sobolev.assemble(g, e, 2.0, 4.5))
+    gt, lam = solve.projected_gradient(A, C, dE)
+    gs, _ = solve.projected_gradient_schur(A, C, dE)
+    assert np.abs(gt - gs).max() < 1e-10 * np.abs(gt).max()
+    assert np.abs(C @ gt.ravel()).max() < 1e-10 * np.abs(gt).max()

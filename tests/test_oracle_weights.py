@@ -204,3 +204,14 @@ def test_midpoint_energy_brute_force_mpmath(alpha, beta):
     g, e = random_loop(9, seed=17)
     ref = brute_force_midpoint_energy(g, e, alpha, beta)
     assert tpe.midpoint_energy(g, e, alpha, beta) == pytest.approx(ref, rel=1e-13)
+
+
+def test_gram_entries_junction_graph_brute_force_mpmath():
+    # a theta graph: two vertices of degree three joined by three arcs (Sec. 7.3 networks)
+    g, e = gen.theta_graph(3, seed=5, jitter_var=1e-3)
+    assert np.bincount(e.ravel()).max() == 3
+    Bref, B0ref = brute_force_gram(g, e, 2.0, 4.5)
+    B, B0 = S.assemble(g, e, 2.0, 4.5)
+    assert np.abs(B - Bref).max() <= 1e-12 * np.abs(Bref).max()
+    assert np.abs(B0 - B0ref).max() <= 1e-12 * np.abs(B0ref).max()
+    assert np.abs(Bref.sum(1)).max() <= 1e-13 * np.abs(Bref).max()
