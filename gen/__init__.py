@@ -15,4 +15,6 @@ from .curves import (  # noqa: F401
     round_to_f32,
     loop_edges,
     theta_graph,
+    tennis_ball,
+    torus_knot,
 )

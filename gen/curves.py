@@ -23,6 +23,8 @@ __all__ = [
     "packing_batch",
     "round_to_f32",
     "theta_graph",
+    "tennis_ball",
+    "torus_knot",
 ]
 
 
@@ -182,3 +184,29 @@ def theta_graph(n_arc: int = 32, n_arcs: int = 3, seed: int = 0, jitter_var: flo
         ids = [0] + list(range(first, first + n_arc - 1)) + [1]
         edges.extend([ids[q], ids[q + 1]] for q in range(n_arc))
     return np.array(pts), np.array(edges, dtype=np.int32)
+
+
+def tennis_ball(n: int = 256, a: float = 0.6, seed: int = 0, jitter_var: float = 0.0):
+    """Closed curve on the unit sphere: ``(a cos t + b cos 3t, a sin t - b sin 3t,
+    2 sqrt(a b) sin 2t)`` with ``b = 1 - a`` (its squared norm is (a + b)^2 = 1),
+    ``n`` uniform samples of t plus i.i.d. Gaussian jitter of variance ``jitter_var``."""
+    b = 1.0 - a
+    t = 2.0 * np.pi * np.arange(n) / n
+    g = np.stack([a * np.cos(t) + b * np.cos(3 * t), a * np.sin(t) - b * np.sin(3 * t),
+                  2.0 * np.sqrt(a * b) * np.sin(2 * t)], axis=1)
+    if jitter_var > 0:
+        g = g + np.random.default_rng(seed).normal(0.0, np.sqrt(jitter_var), size=g.shape)
+    return g, loop_edges(n)
+
+
+def torus_knot(n: int = 256, p: int = 2, q: int = 3, R: float = 1.0, r: float = 0.4, seed: int = 0,
+               jitter_var: float = 0.0):
+    """(p, q) torus knot on the torus of radii (R, r) about the z axis:
+    ``((R + r cos(q t)) cos(p t), (R + r cos(q t)) sin(p t), r sin(q t))``, ``n``
+    uniform samples of t in [0, 2 pi) plus i.i.d. Gaussian jitter of variance ``jitter_var``."""
+    t = 2.0 * np.pi * np.arange(n) / n
+    g = np.stack([(R + r * np.cos(q * t)) * np.cos(p * t), (R + r * np.cos(q * t)) * np.sin(p * t),
+                  r * np.sin(q * t)], axis=1)
+    if jitter_var > 0:
+        g = g + np.random.default_rng(seed).normal(0.0, np.sqrt(jitter_var), size=g.shape)
+    return g, loop_edges(n)

@@ -15,14 +15,22 @@ Definitions (paper Sec. 7.1 "Constraints and Potentials"):
 * Point: ``Phi_{point,i} = gamma_i - x_i`` (3 rows per pinned vertex i, in
   the order the vertices are given), whose Jacobian is the identity block at
   vertex i and zero elsewhere.
+* Surface: ``Phi_{surface,i} = f(gamma_i)`` for an implicit surface f = 0 (1 row
+  per listed vertex), Jacobian row ``grad f(gamma_i)^T`` at vertex i.  Two
+  surfaces, each by its signed distance (so that |grad f| = 1 and Phi has units
+  of length): a sphere ``f = |x - c| - r`` and a torus about the axis through c
+  along z, ``f = sqrt((rho - R)^2 + (z - c_z)^2) - r`` with rho the distance
+  from that axis.
 * Loop length: the total-length constraint applied to every connected
   component (closed loop) separately, ``Phi_q = L0_q - sum_{I in q} l_I``
   (one row per component, components ordered by their smallest vertex), as a
   packing of several curves keeps each curve's length.
 
-Rows are stacked in the order barycenter, total length, points, edge lengths,
-loop lengths.  Points are passed as ``points=(vertices, targets)`` beside the
-flags (no flag of their own: an empty vertex list is no point constraint).
+Rows are stacked in the order barycenter, total length, points, surface, edge
+lengths, loop lengths.  Points are passed as ``points=(vertices, targets)`` and
+surfaces as ``surface=(kind, params, vertices)`` (kind SPHERE with params
+(c_x, c_y, c_z, r), or TORUS with (c_x, c_y, c_z, R, r)) beside the flags (no
+flag of their own: an empty vertex list is no such constraint).
 Vectors in R^{3|V|} are vertex-major: entry ``3 v + c`` is coordinate c of
 vertex v.
 """
@@ -33,13 +41,32 @@ import numpy as np
 
 from .tpe import edge_geometry
 
-__all__ = ["BARYCENTER", "TOTAL_LENGTH", "EDGE_LENGTH", "LOOP_LENGTH", "reference_values", "components",
-           "loop_lengths", "evaluate", "jacobian_sparse"]
+__all__ = ["BARYCENTER", "TOTAL_LENGTH", "EDGE_LENGTH", "LOOP_LENGTH", "SPHERE", "TORUS", "reference_values",
+           "components", "loop_lengths", "surface_value", "evaluate", "jacobian_sparse"]
 
 BARYCENTER = 1
 TOTAL_LENGTH = 2
 EDGE_LENGTH = 4
 LOOP_LENGTH = 8
+SPHERE = 1
+TORUS = 2
+
+
+def surface_value(kind, params, x):
+    """(f(x), grad f(x)) of the implicit surface at the points x [m][3]."""
+    x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+    p = np.asarray(params, dtype=np.float64)
+    d = x - p[:3]
+    if kind == SPHERE:
+        r = np.linalg.norm(d, axis=1)
+        return r - p[3], d / r[:, None]
+    if kind == TORUS:
+        rho = np.hypot(d[:, 0], d[:, 1])
+        a = rho - p[3]
+        q = np.hypot(a, d[:, 2])
+        grad = np.stack([a / q * d[:, 0] / rho, a / q * d[:, 1] / rho, d[:, 2] / q], axis=1)
+        return q - p[4], grad
+    raise ValueError("unknown surface kind")
 
 
 def reference_values(gamma, edges):
@@ -78,10 +105,11 @@ def loop_lengths(gamma, edges):
     return np.bincount(comp, weights=ell)
 
 
-def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True, Lq=None, points=None):
+def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True, Lq=None, points=None, surface=None):
     """(Phi, C) for the constraint set ``mask`` (bitwise OR of the flags);
     ``Lq`` are the loop-length targets, ``points`` = (vertices, targets [m][3])
-    the pinned vertices."""
+    the pinned vertices, ``surface`` = (kind, params, vertices) the vertices
+    held on an implicit surface."""
     g = np.asarray(gamma, dtype=np.float64)
     e = np.asarray(edges)
     nV, nE = len(g), len(e)
@@ -113,6 +141,15 @@ def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True, Lq=No
             for j, v in enumerate(pv):
                 Cp[3 * j:3 * j + 3, 3 * v:3 * v + 3] = np.eye(3)
             jacs.append(Cp)
+    if surface is not None and len(surface[2]):
+        sv = np.asarray(surface[2], dtype=np.int64)
+        f, grad = surface_value(surface[0], surface[1], g[sv])
+        phis.append(f)
+        if jacobian:
+            Cs = np.zeros((len(sv), 3 * nV))
+            for j, v in enumerate(sv):
+                Cs[j, 3 * v:3 * v + 3] = grad[j]
+            jacs.append(Cs)
     if mask & EDGE_LENGTH:
         phis.append(l0 - ell)
         if jacobian:

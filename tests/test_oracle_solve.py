@@ -281,3 +281,57 @@ def test_junction_graph_constraints_and_saddle():
     gs, _ = solve.projected_gradient_schur(A, C, dE)
     assert np.abs(gt - gs).max() < 1e-10 * np.abs(gt).max()
     assert np.abs(C @ gt.ravel()).max() < 1e-10 * np.abs(gt).max()
+
+
+# --- surface constraints (Sec. 7.1) -----------------------------------------
+
+
+def test_surface_values_closed_forms():
+    c = np.array([0.3, -0.2, 0.5])
+    u = np.array([2.0, -1.0, 2.0]) / 3.0
+    f, gr = cons.surface_value(cons.SPHERE, [*c, 1.5], c + (1.5 + 0.01) * u)
+    assert f[0] == pytest.approx(0.01, abs=1e-14) and np.allclose(gr[0], u, atol=1e-14)
+    R, r = 1.0, 0.4
+    pts = c + np.array([[R + r + 0.02, 0.0, 0.0], [0.0, R, r + 0.03], [-(R - r - 0.01), 0.0, 0.0]])
+    f, gr = cons.surface_value(cons.TORUS, [*c, R, r], pts)
+    assert np.allclose(f, [0.02, 0.03, 0.01], atol=1e-14)
+    assert np.allclose(gr, [[1, 0, 0], [0, 0, 1], [1, 0, 0]], atol=1e-14)
+    g, _ = gen.tennis_ball(64)
+    assert np.abs(cons.surface_value(cons.SPHERE, [0, 0, 0, 1.0], g)[0]).max() < 1e-14
+    g, _ = gen.torus_knot(64, R=R, r=r)
+    assert np.abs(cons.surface_value(cons.TORUS, [0, 0, 0, R, r], g)[0]).max() < 1e-14
+
+
+@pytest.mark.parametrize("kind", ["sphere", "torus"])
+def test_surface_jacobian_gradient_and_step(kind):
+    if kind == "sphere":
+        g, e = gen.tennis_ball(48)
+        surf = (cons.SPHERE, [0.0, 0.0, 0.0, 1.0], np.arange(48))
+    else:
+        g, e = gen.torus_knot(48)
+        surf = (cons.TORUS, [0.0, 0.0, 0.0, 1.0, 0.4], np.arange(0, 48, 2))
+    refs = cons.reference_values(g, e)
+    mask = cons.BARYCENTER | cons.EDGE_LENGTH
+    gj = g + 1e-3 * np.random.default_rng(1).normal(size=g.shape)
+    phi, C = cons.evaluate(gj, e, mask, *refs, surface=surf)
+    h = 1e-6
+    for v, c in [(0, 0), (2, 2), (7, 1)]:
+        gp, gm = gj.copy(), gj.copy()
+        gp[v, c] += h
+        gm[v, c] -= h
+        fd = (cons.evaluate(gp, e, mask, *refs, jacobian=False, surface=surf)[0]
+              - cons.evaluate(gm, e, mask, *refs, jacobian=False, surface=surf)[0]) / (2 * h)
+        assert np.allclose(C[:, 3 * v + c], fd, rtol=1e-7, atol=1e-8)
+    # at a curve on the surface the projected gradient is tangent to it at every held vertex
+    _, dE = tpe.differential(g, e, 2.0, 4.5)
+    A = sum(sobolev.assemble(g, e, 2.0, 4.5))
+    _, C = cons.evaluate(g, e, mask, *refs, surface=surf)
+    gt, _ = solve.projected_gradient(A, C, dE)
+    gs, _ = solve.projected_gradient_schur(A, C, dE)
+    assert np.abs(gt - gs).max() < 1e-10 * np.abs(gt).max()
+    _, nrm = cons.surface_value(surf[0], surf[1], g[surf[2]])
+    assert np.abs((gt[surf[2]] * nrm).sum(1)).max() < 1e-10 * np.abs(gt).max()
+    new, info = solve.step(g, e, 2.0, 4.5, mask, refs, surface=surf)
+    assert info["ok"] and info["E1"] < info["E0"]
+    f, _ = cons.surface_value(surf[0], surf[1], new[surf[2]])
+    assert np.abs(f).max() <= 1e-10 * refs[2].mean()
