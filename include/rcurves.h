@@ -306,7 +306,8 @@ rc_status rc_set_constraints(rc_ctx* ctx, uint32_t mask, const double* gamma_ref
 
 /* Point constraints (Sec. 7.1): Phi_{point,i} = gamma_i - x_i, 3 rows per
  * pinned vertex i, whose Jacobian is the identity block at vertex i.
- * vertices_h: HOST int32 [npt], distinct vertex indices; targets_h: HOST
+ * vertices_h: HOST int32 [npt], distinct vertex indices, none of them held
+ * on a surface (rc_set_surface_constraints); targets_h: HOST
  * double [npt][3] the points x_i.  npt in [0, nV]; 0 removes them.  They
  * join the set chosen by rc_set_constraints (which keeps them) in every
  * solver, the projection and the step; the other constraints keep their
@@ -317,15 +318,35 @@ rc_status rc_set_constraints(rc_ctx* ctx, uint32_t mask, const double* gamma_ref
  * and is given a zero multiplier.  On a coarser multigrid level the coarse
  * vertices a pinned vertex interpolates from are pinned (coarsening stops
  * before a level would be more than a quarter pinned).
- * Errors: RC_ERR_ARG (npt out of range, null pointers, a vertex out of range
- * or given twice, a non-finite target).  Pins that leave the remaining
+ * Errors: RC_ERR_ARG (npt out of range, null pointers, a vertex out of range,
+ * given twice or held on a surface, a non-finite target).  Pins that leave the remaining
  * constraints dependent (for instance every vertex pinned with the barycenter
  * constraint) give RC_ERR_SINGULAR in the solve. */
 rc_status rc_set_point_constraints(rc_ctx* ctx, int32_t npt, const int32_t* vertices_h, const double* targets_h);
 
+/* Surface constraints (Sec. 7.1): Phi_{surface,i} = f(gamma_i), one row per
+ * held vertex i, with Jacobian row grad f(gamma_i)^T at vertex i; f is the
+ * signed distance of
+ *   RC_SURFACE_SPHERE: params_h = (c_x, c_y, c_z, r), f = |x - c| - r, r > 0;
+ *   RC_SURFACE_TORUS:  params_h = (c_x, c_y, c_z, R, r), the torus about the
+ *     z axis through c, f = sqrt((rho - R)^2 + (z - c_z)^2) - r with rho the
+ *     distance from that axis, R > r > 0.
+ * vertices_h: HOST int32 [n] distinct vertex indices, none of them pinned;
+ * n in [0, nV], 0 removes the constraint.  Like the point constraints they
+ * are eliminated in the iterative solvers (the projector's W_v = I - n_v n_v^T
+ * at a held vertex, n_v the unit normal at gamma_v) and join every solver,
+ * the projection and the step; on a coarser multigrid level a held vertex
+ * that the coarsening keeps stays held.  Errors: RC_ERR_ARG (n out of
+ * range, unknown kind, null pointers, non-finite or out-of-range parameters,
+ * a vertex out of range, given twice or pinned). */
+enum { RC_SURFACE_SPHERE = 1, RC_SURFACE_TORUS = 2 };
+rc_status rc_set_surface_constraints(rc_ctx* ctx, int32_t kind, const double* params_h, int32_t n,
+                                     const int32_t* vertices_h);
+
 /* Phi(gamma) (Sec. 7.1) in the row order barycenter (3), total length (1),
- * points (3 each, in the order given), edge lengths (nE), restricted to the
- * active set.  phi: device double [k]. */
+ * points (3 each, in the order given), surface (1 per held vertex, in the
+ * order given), edge lengths (nE), restricted to the active set.  phi:
+ * device double [k]. */
 rc_status rc_constraint_values(rc_ctx* ctx, const double* gamma, double* phi);
 
 /* Number of active constraint rows k. */

@@ -9,6 +9,8 @@ in the HIP kernels of ``csrc/``.
 from ._lib import (  # noqa: F401
     RC_C_BARYCENTER,
     RC_C_EDGE_LENGTH,
+    RC_SURFACE_SPHERE,
+    RC_SURFACE_TORUS,
     RC_C_TOTAL_LENGTH,
     RC_F32,
     RC_F64,

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "librcurves.so")
 
 RC_F64, RC_F32 = 0, 1
 RC_C_BARYCENTER, RC_C_TOTAL_LENGTH, RC_C_EDGE_LENGTH = 1, 2, 4
+RC_SURFACE_SPHERE, RC_SURFACE_TORUS = 1, 2
 RC_SOLVE_DENSE, RC_SOLVE_PCG_JACOBI, RC_SOLVE_PCG_MG, RC_SOLVE_PCG_LEARNED, RC_SOLVE_MG_FMG = 0, 1, 2, 4, 5
 
 STATUS = {
@@ -29,7 +30,8 @@ STATUS = {
 EXPORTED = [
     "rc_default_solve_opts", "rc_default_ls_opts", "rc_last_error", "rc_create", "rc_destroy", "rc_energy",
     "rc_differential", "rc_sobolev_apply", "rc_sobolev_apply_prec", "rc_sobolev_diag", "rc_assemble_dense",
-    "rc_set_constraints", "rc_set_point_constraints", "rc_constraint_values", "rc_constraint_count", "rc_project",
+    "rc_set_constraints", "rc_set_point_constraints", "rc_set_surface_constraints", "rc_constraint_values",
+    "rc_constraint_count", "rc_project",
     "rc_sobolev_gradient",
     "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_bh_last_work", "rc_midpoint_differential",
     "rc_profile_enable", "rc_profile_read", "rc_lowp_assemble", "rc_lowp_apply", "rc_set_obstacle",
@@ -113,6 +115,7 @@ def load():
         "rc_assemble_dense": (I32, [P, P, P]),
         "rc_set_constraints": (I32, [P, U32, P, P, D, P]),
         "rc_set_point_constraints": (I32, [P, I32, P, P]),
+        "rc_set_surface_constraints": (I32, [P, I32, P, I32, P]),
         "rc_constraint_values": (I32, [P, P, P]),
         "rc_constraint_count": (I32, [P]),
         "rc_project": (I32, [P, P, P, P]),
@@ -325,6 +328,15 @@ class Context:
         self._px = (C.c_double * max(len(t), 1))(*t)
         _check(load().rc_set_point_constraints(self.h, len(v), C.cast(self._pv, C.c_void_p),
                                                C.cast(self._px, C.c_void_p)))
+
+    def rc_set_surface_constraints(self, kind=0, params=(), vertices=()):
+        """Hold vertices on the sphere (kind 1, params c, r) or torus (kind 2, params c, R, r)."""
+        v = [int(i) for i in vertices]
+        p = [float(x) for x in params]
+        self._sv = (C.c_int32 * max(len(v), 1))(*v)
+        self._sp = (C.c_double * max(len(p), 5))(*p)
+        _check(load().rc_set_surface_constraints(self.h, int(kind), C.cast(self._sp, C.c_void_p), len(v),
+                                                 C.cast(self._sv, C.c_void_p)))
 
     def rc_constraint_count(self):
         return int(load().rc_constraint_count(self.h))

@@ -342,43 +342,18 @@ rc_status rc_set_constraints(rc_ctx* c, uint32_t mask, const double* gamma_ref, 
   RC_TRY(sync(c));
   mg_free(c);  // the coarse levels carry constraints of the same kinds
   dense_free(c->dense);
-  RC_TRY(cons_alloc(c, c->curve, c->cons, mask, c->pts));
+  RC_TRY(cons_alloc(c, c->curve, c->cons, mask, c->pts, &c->surf));
   if (!c->pts.empty())
     RC_HIP(hipMemcpy(c->cons.ptx, c->pts_x.data(), sizeof(double) * c->pts_x.size(), hipMemcpyHostToDevice));
   if (mask == 0) return RC_OK;
   return cons_set_targets(c, gamma_ref, x0_h, total_len0, edge_len0);
 }
 
-rc_status rc_set_point_constraints(rc_ctx* c, int32_t npt, const int32_t* vertices_h, const double* targets_h) {
-  RC_TRY(check_ctx(c));
-  RC_TRY(no_batch(c, "rc_set_point_constraints"));
-  if (npt < 0 || npt > c->nV || (npt > 0 && (!vertices_h || !targets_h))) {
-    set_error("point constraints: npt must lie in [0, nV], with host vertices and targets when positive");
-    return RC_ERR_ARG;
-  }
-  std::vector<int> pts(vertices_h, vertices_h + npt);
-  std::vector<double> px(targets_h, targets_h + 3 * (size_t)npt);
-  std::vector<int> sorted = pts;
-  std::sort(sorted.begin(), sorted.end());
-  if (npt > 0 && (sorted.front() < 0 || sorted.back() >= c->nV ||
-                  std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())) {
-    set_error("point constraints: vertex out of range or given twice");
-    return RC_ERR_ARG;
-  }
-  for (double v : px)
-    if (!std::isfinite(v)) {
-      set_error("point constraints: non-finite target");
-      return RC_ERR_ARG;
-    }
+namespace rc {
+// Re-lays the finest level's constraint rows for the context's points and surface, keeping the
+// targets of the other constraints.
+static rc_status relay_constraints(rc_ctx* c) {
   RC_TRY(sync(c));
-  // Phi and its negation in the projection (2 k values)
-  const size_t kmax = (size_t)c->nE + 4 + 3 * (size_t)npt;
-  if (kmax > c->phi_cap) {
-    hipFree(c->phi);
-    RC_TRY(dalloc(&c->phi, 2 * kmax));
-    c->phi_cap = kmax;
-  }
-  // re-lay the finest level's rows, keeping the other constraints' targets
   Cons& k = c->cons;
   const uint32_t mask = k.mask;
   const double total0 = k.total0;
@@ -389,16 +364,93 @@ rc_status rc_set_point_constraints(rc_ctx* c, int32_t npt, const int32_t* vertic
     len0.resize(c->nE);
     RC_TRY(fetch(c, k.len0, len0.data(), c->nE));
   }
+  // Phi and its negation in the projection (2 k values)
+  const size_t kmax = (size_t)c->nE + 4 + 3 * c->pts.size() + c->surf.verts.size();
+  if (kmax > c->phi_cap) {
+    hipFree(c->phi);
+    RC_TRY(dalloc(&c->phi, 2 * kmax));
+    c->phi_cap = kmax;
+  }
   mg_free(c);
   dense_free(c->dense);
-  c->pts = pts;
-  c->pts_x = px;
-  RC_TRY(cons_alloc(c, c->curve, k, mask, c->pts));
+  RC_TRY(cons_alloc(c, c->curve, k, mask, c->pts, &c->surf));
   k.total0 = total0;
   RC_HIP(hipMemcpy(k.x0, x0, sizeof(double) * 3, hipMemcpyHostToDevice));
   if (!len0.empty()) RC_HIP(hipMemcpy(k.len0, len0.data(), sizeof(double) * c->nE, hipMemcpyHostToDevice));
-  if (npt) RC_HIP(hipMemcpy(k.ptx, px.data(), sizeof(double) * px.size(), hipMemcpyHostToDevice));
+  if (!c->pts.empty())
+    RC_HIP(hipMemcpy(k.ptx, c->pts_x.data(), sizeof(double) * c->pts_x.size(), hipMemcpyHostToDevice));
   return RC_OK;
+}
+
+// distinct indices in [0, nV), none of them in `other`
+static bool valid_vertex_set(const std::vector<int>& v, int nV, const std::vector<int>& other) {
+  std::vector<int> sorted = v;
+  std::sort(sorted.begin(), sorted.end());
+  if (!sorted.empty() && (sorted.front() < 0 || sorted.back() >= nV ||
+                          std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()))
+    return false;
+  for (int u : other)
+    if (std::binary_search(sorted.begin(), sorted.end(), u)) return false;
+  return true;
+}
+}  // namespace rc
+
+rc_status rc_set_point_constraints(rc_ctx* c, int32_t npt, const int32_t* vertices_h, const double* targets_h) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_set_point_constraints"));
+  if (npt < 0 || npt > c->nV || (npt > 0 && (!vertices_h || !targets_h))) {
+    set_error("point constraints: npt must lie in [0, nV], with host vertices and targets when positive");
+    return RC_ERR_ARG;
+  }
+  std::vector<int> pts(vertices_h, vertices_h + npt);
+  std::vector<double> px(targets_h, targets_h + 3 * (size_t)npt);
+  if (!valid_vertex_set(pts, c->nV, c->surf.verts)) {
+    set_error("point constraints: vertex out of range, given twice, or held on the surface");
+    return RC_ERR_ARG;
+  }
+  for (double v : px)
+    if (!std::isfinite(v)) {
+      set_error("point constraints: non-finite target");
+      return RC_ERR_ARG;
+    }
+  c->pts = pts;
+  c->pts_x = px;
+  return relay_constraints(c);
+}
+
+rc_status rc_set_surface_constraints(rc_ctx* c, int32_t kind, const double* params_h, int32_t n,
+                                     const int32_t* vertices_h) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_set_surface_constraints"));
+  if (n < 0 || n > c->nV || (n > 0 && (!vertices_h || !params_h)) ||
+      (n > 0 && kind != RC_SURFACE_SPHERE && kind != RC_SURFACE_TORUS)) {
+    set_error("surface constraints: n must lie in [0, nV], with a known kind, host parameters and vertices");
+    return RC_ERR_ARG;
+  }
+  SurfSpec sp;
+  if (n > 0) {
+    sp.kind = kind;
+    const int np_ = kind == RC_SURFACE_SPHERE ? 4 : 5;
+    for (int q = 0; q < np_; ++q) {
+      sp.par[q] = params_h[q];
+      if (!std::isfinite(sp.par[q])) {
+        set_error("surface constraints: non-finite parameter");
+        return RC_ERR_ARG;
+      }
+    }
+    const bool ok = kind == RC_SURFACE_SPHERE ? sp.par[3] > 0.0 : (sp.par[4] > 0.0 && sp.par[3] > sp.par[4]);
+    if (!ok) {
+      set_error("surface constraints: need r > 0 (sphere) or R > r > 0 (torus)");
+      return RC_ERR_ARG;
+    }
+    sp.verts.assign(vertices_h, vertices_h + n);
+    if (!valid_vertex_set(sp.verts, c->nV, c->pts)) {
+      set_error("surface constraints: vertex out of range, given twice, or pinned");
+      return RC_ERR_ARG;
+    }
+  }
+  c->surf = sp;
+  return relay_constraints(c);
 }
 
 int32_t rc_constraint_count(const rc_ctx* c) { return c ? c->cons.k : 0; }

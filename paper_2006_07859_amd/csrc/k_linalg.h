@@ -48,13 +48,15 @@ void cons_phi_edge(const double* geo, const double* x0, int nE, const double* le
 void cons_border_rows(const double* geo, const int* inc_off, const int* inc, const int2* edges, const double* x0,
                       int nV, int bary, int total, const int* cut_edge, int ncut, double* rows, int nrows,
                       hipStream_t s);
-// point constraints by elimination: weights (w or 1) times the free mask, masking, unit zero diagonals
+// point and surface constraints by elimination: weights (w or 1) times the free mask, x_v <- W_v x_v
+// (W_v = w_v (I - n_v n_v^T), nrm may be null), unit zero diagonals
 void free_weights(const double* w, const double* free, int nV, double* out, hipStream_t s);
-void mask_vertices(double* x, const double* free, int nV, hipStream_t s);
+void mask_vertices(double* x, const double* w, const double* nrm, int nV, hipStream_t s);
 void unit_zero_diag(double* A, int n, hipStream_t s);
 void cons_path_coeffs(const double* geo, const int2* edges, const int* path_edge, const int* path_prev, int np,
-                      const double* w, double* ta, double* td, double* tc, hipStream_t s);
-void cons_scale_rows(const double* rows, const double* w, int nV, int nrows, double* out, hipStream_t s);
+                      const double* w, const double* nrm, double* ta, double* td, double* tc, hipStream_t s);
+void cons_scale_rows(const double* rows, const double* w, const double* nrm, int nV, int nrows, double* out,
+                     hipStream_t s);
 void cons_path_apply(const double* geo, const int2* edges, const int* path_edge, int np, const double* V, int nV,
                      int m, double* W, hipStream_t s);
 void cons_apply_CT(const double* geo, const int* inc_off, const int* inc, const int* edge_path_row,
@@ -98,6 +100,9 @@ struct ProjData {
   // out = beta prev + scale M in with M = W - W C^T (C W C^T)^-1 C W, the
   // inverse of W^-1 on the null space of C; w null: M = P
   const double* w = nullptr;
+  // per-vertex unit normals [nV][3] (zero where a vertex has none): W_v = w_v (I - n_v n_v^T), the
+  // tangent plane of a surface constraint eliminated like a weight
+  const double* nrm = nullptr;
   double scale = 1.0, beta = 0.0;
   const double* prev = nullptr;  // null: no beta term (prev may alias out)
   double* xacc = nullptr;        // also xacc = out (xset) or xacc += out, per entry

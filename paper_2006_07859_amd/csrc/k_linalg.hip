@@ -641,15 +641,31 @@ void cons_border_rows(const double* geo, const int* inc_off, const int* inc, con
 // Tridiagonal coefficients of C_p W C_p^T over the path rows (chain order),
 // W = diag(w) per vertex (w null: the identity): diag w_i1 + w_i2 (|T_I| = 1),
 // off-diagonal s_I(v) s_J(v) w_v T_I.T_J for consecutive rows sharing v.
+// T_I^T W_v T_J with W_v = w_v (I - n_v n_v^T) (unit tangents)
+__device__ __forceinline__ double tw_dot(const double* __restrict__ w, const double* __restrict__ nrm, int v,
+                                         const double* ti, const double* tj) {
+  double d = ti[0] * tj[0] + ti[1] * tj[1] + ti[2] * tj[2];
+  if (nrm) {
+    const double* n = nrm + 3 * (size_t)v;
+    d -= (n[0] * ti[0] + n[1] * ti[1] + n[2] * ti[2]) * (n[0] * tj[0] + n[1] * tj[1] + n[2] * tj[2]);
+  }
+  return w ? w[v] * d : d;
+}
+
 __global__ void k_path_coeffs(const double* __restrict__ geo, const int2* __restrict__ edges,
                               const int* __restrict__ path_edge, const int* __restrict__ path_prev, int np,
-                              const double* __restrict__ w, double* __restrict__ ta, double* __restrict__ td,
-                              double* __restrict__ tc) {
+                              const double* __restrict__ w, const double* __restrict__ nrm, double* __restrict__ ta,
+                              double* __restrict__ td, double* __restrict__ tc) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= np) return;
   const int I = path_edge[k];
   const int2 ei = edges[I];
-  td[k] = w ? w[ei.x] + w[ei.y] : 2.0;
+  if (nrm) {
+    const double* ti = geo + 8 * (size_t)I + 1;
+    td[k] = tw_dot(w, nrm, ei.x, ti, ti) + tw_dot(w, nrm, ei.y, ti, ti);
+  } else {
+    td[k] = w ? w[ei.x] + w[ei.y] : 2.0;
+  }
   // both ends of zero weight (pinned vertices): the row of C W C^T is zero and its constraint
   // holds for every admissible vector; a unit diagonal gives it a zero multiplier (pseudo-inverse)
   if (td[k] == 0.0) td[k] = 1.0;
@@ -665,7 +681,8 @@ __global__ void k_path_coeffs(const double* __restrict__ geo, const int2* __rest
     else { si = -1; sj = -1; sv = ei.y; }
     const double* gi = geo + 8 * (size_t)I;
     const double* gj = geo + 8 * (size_t)J;
-    const double v = si * sj * (gi[1] * gj[1] + gi[2] * gj[2] + gi[3] * gj[3]) * (w ? w[sv] : 1.0);
+    const double v = nrm ? si * sj * tw_dot(w, nrm, sv, gi + 1, gj + 1)
+                         : si * sj * (gi[1] * gj[1] + gi[2] * gj[2] + gi[3] * gj[3]) * (w ? w[sv] : 1.0);
     ta[k] = v;
     tc[k - 1] = v;
   } else {
@@ -675,25 +692,40 @@ __global__ void k_path_coeffs(const double* __restrict__ geo, const int2* __rest
 }
 
 void cons_path_coeffs(const double* geo, const int2* edges, const int* path_edge, const int* path_prev, int np,
-                      const double* w, double* ta, double* td, double* tc, hipStream_t s) {
+                      const double* w, const double* nrm, double* ta, double* td, double* tc, hipStream_t s) {
   // tc[k-1] is written by row k; rows without a predecessor leave tc[k-1] to be zero
   hipMemsetAsync(tc, 0, sizeof(double) * np, s);
   hipLaunchKernelGGL(k_path_coeffs, dim3(cdiv(np, 256)), dim3(256), 0, s, geo, edges, path_edge, path_prev, np, w,
-                     ta, td, tc);
+                     nrm, ta, td, tc);
 }
 
-// out[r][v][c] = rows[r][v][c] w[v] for nrows rows
-__global__ void k_scale_rows(const double* __restrict__ rows, const double* __restrict__ w, int nV, int nrows,
-                             double* __restrict__ out) {
+// out[r][v] = W_v rows[r][v] for nrows rows, W_v = w[v] (I - n_v n_v^T) (nrm may be null)
+__global__ void k_scale_rows(const double* __restrict__ rows, const double* __restrict__ w,
+                             const double* __restrict__ nrm, int nV, int nrows, double* __restrict__ out) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)nrows * nV * 3) return;
-  out[i] = rows[i] * w[(i / 3) % nV];
+  if (i >= (size_t)nrows * nV) return;
+  const int v = (int)(i % nV);
+  const double* r = rows + 3 * i;
+  double x0 = r[0], x1 = r[1], x2 = r[2];
+  if (nrm) {
+    const double* n = nrm + 3 * (size_t)v;
+    const double p = n[0] * x0 + n[1] * x1 + n[2] * x2;
+    x0 -= p * n[0];
+    x1 -= p * n[1];
+    x2 -= p * n[2];
+  }
+  const double wv = w[v];
+  out[3 * i] = x0 * wv;
+  out[3 * i + 1] = x1 * wv;
+  out[3 * i + 2] = x2 * wv;
 }
 
-void cons_scale_rows(const double* rows, const double* w, int nV, int nrows, double* out, hipStream_t s) {
-  const size_t n = (size_t)nrows * nV * 3;
+void cons_scale_rows(const double* rows, const double* w, const double* nrm, int nV, int nrows, double* out,
+                     hipStream_t s) {
+  const size_t n = (size_t)nrows * nV;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rows, w, nV, nrows, out);
+  hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rows, w, nrm, nV, nrows,
+                     out);
 }
 
 // w[k] = C_{path_edge[k]} v = T_I . (v_i1 - v_i2), for m vectors (v_r = V + r*3nV, w_r = W + r*np).
@@ -804,6 +836,23 @@ void cons_sub_Zy(const double* Z, const double* yb, int nb, int np, double* yp, 
 // load before the gathers.
 constexpr int kProjSlots = 2 * kProjMaxBorder;
 
+// x <- W_v x with W_v = w_v (I - n_v n_v^T) (d.w null: w_v = 1; d.nrm null: no normal part)
+__device__ __forceinline__ void proj_w_apply(const ProjData& d, int v, double& x0, double& x1, double& x2) {
+  if (d.nrm) {
+    const double* n = d.nrm + 3 * (size_t)v;
+    const double p = n[0] * x0 + n[1] * x1 + n[2] * x2;
+    x0 -= p * n[0];
+    x1 -= p * n[1];
+    x2 -= p * n[2];
+  }
+  if (d.w) {
+    const double s = d.w[v];
+    x0 *= s;
+    x1 *= s;
+    x2 *= s;
+  }
+}
+
 // w = C_I x for path row i
 __device__ __forceinline__ double proj_row_value(const ProjData& d, int i, const double* __restrict__ x) {
   double t0, t1, t2;
@@ -824,6 +873,13 @@ __device__ __forceinline__ double proj_row_value(const ProjData& d, int i, const
     t2 = g[3];
     a = e.x;
     b = e.y;
+  }
+  if (d.nrm) {  // C (W x) with the normal parts
+    double a0 = x[3 * a], a1 = x[3 * a + 1], a2 = x[3 * a + 2];
+    double b0 = x[3 * b], b1 = x[3 * b + 1], b2 = x[3 * b + 2];
+    proj_w_apply(d, a, a0, a1, a2);
+    proj_w_apply(d, b, b0, b1, b2);
+    return t0 * (a0 - b0) + t1 * (a1 - b1) + t2 * (a2 - b2);
   }
   if (d.w) {  // C (W x)
     const double wa = d.w[a], wb = d.w[b];
@@ -860,6 +916,17 @@ __global__ __launch_bounds__(kSpThreads) void k_proj_rows(const ProjData d, cons
   }
   // border dot products over the vertices, spread over the workgroups
   for (int i = blk * kSpThreads + t; i < nV; i += gridDim.x * kSpThreads) {
+    if (d.nrm) {  // rows . (W x)
+      double x0 = x[3 * i], x1 = x[3 * i + 1], x2 = x[3 * i + 2];
+      proj_w_apply(d, i, x0, x1, x2);
+#pragma unroll
+      for (int r = 0; r < kProjMaxBorder; ++r)
+        if (r < nb) {
+          const double* rv = d.rows + ((size_t)r * nV + i) * 3;
+          acc[r] += rv[0] * x0 + rv[1] * x1 + rv[2] * x2;
+        }
+      continue;
+    }
     const double wi = d.w ? d.w[i] : 1.0;
 #pragma unroll
     for (int r = 0; r < kProjMaxBorder; ++r)
@@ -1006,9 +1073,14 @@ __device__ __forceinline__ void apply_CT_z_vertex(const ProjData& d, int v, cons
   for (int r = 0; r < kProjMaxBorder; ++r)
     if (r < nb)
       for (int cc = 0; cc < 3; ++cc) acc[cc] += ybr[r] * d.rows[((size_t)r * d.nV + v) * 3 + cc];
-  const double sw = d.scale * (d.w ? d.w[v] : 1.0);
+  double res[3] = {in[3 * v] - acc[0], in[3 * v + 1] - acc[1], in[3 * v + 2] - acc[2]};
+  double sw = d.scale;
+  if (d.nrm)  // W_v (in - C^T y) with the normal part
+    proj_w_apply(d, v, res[0], res[1], res[2]);
+  else if (d.w)
+    sw *= d.w[v];
   for (int cc = 0; cc < 3; ++cc) {
-    const double o0 = sw * (in[3 * v + cc] - acc[cc]);
+    const double o0 = sw * res[cc];
     const double o = d.prev ? d.beta * d.prev[3 * v + cc] + o0 : o0;
     out[3 * v + cc] = o;
     val[cc] = o;
@@ -1116,8 +1188,19 @@ __device__ __forceinline__ void proj_small_vertex(const ProjData& d, int t, doub
       a1 += ybs[r] * rv[1];
       a2 += ybs[r] * rv[2];
     }
-  const double sw = d.scale * w_t;
-  double o[3] = {sw * (x0 - a0), sw * (x1 - a1), sw * (x2 - a2)};
+  double o[3];
+  if (d.nrm) {  // scale W_t (x - C^T y)
+    double r0 = x0 - a0, r1 = x1 - a1, r2 = x2 - a2;
+    proj_w_apply(d, t, r0, r1, r2);
+    o[0] = d.scale * r0;
+    o[1] = d.scale * r1;
+    o[2] = d.scale * r2;
+  } else {
+    const double sw = d.scale * w_t;
+    o[0] = sw * (x0 - a0);
+    o[1] = sw * (x1 - a1);
+    o[2] = sw * (x2 - a2);
+  }
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc) {
     if (d.prev) o[cc] += d.beta * pin[cc];
@@ -1174,16 +1257,33 @@ __global__ __launch_bounds__(kTriThreads) void k_proj_small(const ProjData d, co
   double wv = 0.0;
   if (row) {
     const int a = pr_t.ends.x, b = pr_t.ends.y;
-    const double wa = d.w ? d.w[a] : 1.0, wb = d.w ? d.w[b] : 1.0;
-    wv = pr_t.t[0] * (wa * x[3 * a] - wb * x[3 * b]) + pr_t.t[1] * (wa * x[3 * a + 1] - wb * x[3 * b + 1]) +
-         pr_t.t[2] * (wa * x[3 * a + 2] - wb * x[3 * b + 2]);
+    if (d.nrm) {
+      double a0 = x[3 * a], a1 = x[3 * a + 1], a2 = x[3 * a + 2];
+      double b0 = x[3 * b], b1 = x[3 * b + 1], b2 = x[3 * b + 2];
+      proj_w_apply(d, a, a0, a1, a2);
+      proj_w_apply(d, b, b0, b1, b2);
+      wv = pr_t.t[0] * (a0 - b0) + pr_t.t[1] * (a1 - b1) + pr_t.t[2] * (a2 - b2);
+    } else {
+      const double wa = d.w ? d.w[a] : 1.0, wb = d.w ? d.w[b] : 1.0;
+      wv = pr_t.t[0] * (wa * x[3 * a] - wb * x[3 * b]) + pr_t.t[1] * (wa * x[3 * a + 1] - wb * x[3 * b + 1]) +
+           pr_t.t[2] * (wa * x[3 * a + 2] - wb * x[3 * b + 2]);
+    }
 #pragma unroll
     for (int r = 0; r < kProjMaxBorder; ++r)
       if (r < nb) acc[kProjMaxBorder + r] = d.Z[(size_t)r * np + t] * wv;
   }
   const double x0 = vert ? x[3 * t] : 0.0, x1 = vert ? x[3 * t + 1] : 0.0, x2 = vert ? x[3 * t + 2] : 0.0;
   const double w_t = (vert && d.w) ? d.w[t] : 1.0;
-  if (vert) {
+  if (vert && d.nrm) {  // rows . (W x)
+    double y0 = x0, y1 = x1, y2 = x2;
+    proj_w_apply(d, t, y0, y1, y2);
+#pragma unroll
+    for (int r = 0; r < kProjMaxBorder; ++r)
+      if (r < nb) {
+        const double* rv = d.rows + ((size_t)r * nV + t) * 3;
+        acc[r] = rv[0] * y0 + rv[1] * y1 + rv[2] * y2;
+      }
+  } else if (vert) {
 #pragma unroll
     for (int r = 0; r < kProjMaxBorder; ++r)
       if (r < nb) {
@@ -1381,14 +1481,27 @@ void free_weights(const double* w, const double* free, int nV, double* out, hipS
   hipLaunchKernelGGL(k_free_weights, dim3(cdiv(nV, 256)), dim3(256), 0, s, w, free, nV, out);
 }
 
-// x[v] *= free[v] (3 components)
-__global__ void k_mask_vertices(double* __restrict__ x, const double* __restrict__ free, int nV) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 3 * nV) x[i] *= free[i / 3];
+// x_v <- W_v x_v, W_v = w[v] (I - n_v n_v^T) (nrm may be null)
+__global__ void k_mask_vertices(double* __restrict__ x, const double* __restrict__ w, const double* __restrict__ nrm,
+                                int nV) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nV) return;
+  double x0 = x[3 * v], x1 = x[3 * v + 1], x2 = x[3 * v + 2];
+  if (nrm) {
+    const double* n = nrm + 3 * (size_t)v;
+    const double p = n[0] * x0 + n[1] * x1 + n[2] * x2;
+    x0 -= p * n[0];
+    x1 -= p * n[1];
+    x2 -= p * n[2];
+  }
+  const double s = w[v];
+  x[3 * v] = x0 * s;
+  x[3 * v + 1] = x1 * s;
+  x[3 * v + 2] = x2 * s;
 }
 
-void mask_vertices(double* x, const double* free, int nV, hipStream_t s) {
-  hipLaunchKernelGGL(k_mask_vertices, dim3(cdiv(3 * nV, 256)), dim3(256), 0, s, x, free, nV);
+void mask_vertices(double* x, const double* w, const double* nrm, int nV, hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_vertices, dim3(cdiv(nV, 256)), dim3(256), 0, s, x, w, nrm, nV);
 }
 
 }  // namespace rc

@@ -15,6 +15,20 @@ namespace rc {
 // (barycenter, total length, and the first edge of every loop, whose removal
 // leaves the path rows tridiagonal).  C C^T is solved through the border
 // Schur complement S = K_bb - K_pb^T K_pp^-1 K_pb.
+// Vertices held on an implicit surface (Sec. 7.1, Phi = f(gamma_i)), f the signed distance of a
+// sphere (par = c, r) or of a torus about the z axis through c (par = c, R, r).
+struct SurfSpec {
+  int kind = 0;  // 0 none, RC_SURFACE_SPHERE, RC_SURFACE_TORUS
+  double par[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  std::vector<int> verts;
+  bool operator==(const SurfSpec& o) const {
+    for (int q = 0; q < 5; ++q)
+      if (par[q] != o.par[q]) return false;
+    return kind == o.kind && verts == o.verts;
+  }
+  bool operator!=(const SurfSpec& o) const { return !(*this == o); }
+};
+
 struct Cons {
   uint32_t mask = 0;
   int bary = 0, total = 0, edge = 0;
@@ -24,11 +38,19 @@ struct Cons {
   // F - F C^T (C F C^T)^-1 C F, the weighted projector with W = F (and the smoother's
   // W = D^-1 F), so they add no border rows
   int npt = 0, nbt = 0, nd = 0;         // pinned vertices; barycenter + total rows; rows before the edge rows
+                                        // (nbt + 3 npt + nsf)
   double total0 = 0.0;
   std::vector<int> h_pt;                // pinned vertices, in row order
   int* pt = nullptr;
   double* ptx = nullptr;                // their targets x_i [npt][3]
-  double* free = nullptr;               // [nV] 0 at pinned vertices, else 1 (npt > 0)
+  // surface constraints, eliminated the same way with W_v = w_v (I - n_v n_v^T)
+  SurfSpec surf;
+  int nsf = 0;
+  int* sf = nullptr;                    // [nsf] the held vertices, in row order
+  double* sgrad = nullptr;              // [nsf][3] grad f at the prepared curve
+  double* nrm = nullptr;                // [nV][3] unit normals there (zero at other vertices)
+  bool elim = false;                    // point or surface constraints present
+  double* free = nullptr;               // [nV] 0 at pinned vertices, else 1 (elim)
   double* weff = nullptr;               // [nV] the weights of the prepared factors (w or 1) * free
   std::vector<int> h_path_edge, h_path_prev, h_cut_edge, h_edge_path_row;
   int *path_edge = nullptr, *path_prev = nullptr, *cut_edge = nullptr, *edge_path_row = nullptr;
@@ -185,6 +207,7 @@ struct rc_ctx {
   // point constraints of the finest level (kept across rc_set_constraints)
   std::vector<int> pts;
   std::vector<double> pts_x;
+  rc::SurfSpec surf;
   size_t phi_cap = 0;  // rows the phi buffer holds (twice)
 };
 
@@ -198,7 +221,8 @@ rc_status sync(rc_ctx* c);
 rc_status fetch(rc_ctx* c, const double* dev, double* host, int n);
 bool trace_on();
 
-rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const std::vector<int>& pts = {});
+rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const std::vector<int>& pts = {},
+                     const SurfSpec* surf = nullptr);
 void cons_free(Cons& k);
 rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma, const double* w = nullptr);
 // With pop, the last launch also writes the operand of pop's next product,

@@ -103,39 +103,84 @@ __global__ void k_map_rhs(const double* __restrict__ b, int nbt, int nd, const i
   if (i < ncut) wb[nbt + i] = sign * b[nd + cut_edge[i]];
 }
 
-// With pinned vertices a particular solution of C z = b sets z_P = b_P (the point rows of b)
-// and solves the other rows for the free part: their right-hand side loses C v_P, v_P the
-// point rows placed at their vertices (wp, wb carry the factor sign).  One thread: pins on
-// a shared row are summed in order.
-__global__ void k_pin_rhs(const double* __restrict__ b, int nbt, const int* __restrict__ pt, int npt,
-                          const double* __restrict__ rows, int nb, int nV, const double* __restrict__ geo,
-                          const int* __restrict__ inc_off, const int* __restrict__ inc,
-                          const int* __restrict__ edge_path_row, double* __restrict__ wp, double* __restrict__ wb,
-                          double sign) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  for (int j = 0; j < npt; ++j) {
-    const int p = pt[j];
-    const double v0 = b[nbt + 3 * j], v1 = b[nbt + 3 * j + 1], v2 = b[nbt + 3 * j + 2];
-    for (int r = 0; r < nb; ++r) {
-      const double* rv = rows + ((size_t)r * nV + p) * 3;
-      wb[r] -= sign * (rv[0] * v0 + rv[1] * v1 + rv[2] * v2);
-    }
-    for (int q = inc_off[p]; q < inc_off[p + 1]; ++q) {
-      const int I = inc[q] >> 1;
-      const int pr = edge_path_row[I];
-      if (pr < 0) continue;
-      const double sg = (inc[q] & 1) ? -1.0 : 1.0;  // the edge row: +T_I at i1, -T_I at i2
-      const double* g = geo + 8 * (size_t)I;
-      wp[pr] -= sign * sg * (g[1] * v0 + g[2] * v1 + g[3] * v2);
-    }
+// The implicit surface of a surface constraint by value (kernel argument).
+struct SurfPar {
+  int kind;
+  double p[5];
+};
+
+static SurfPar surf_par(const Cons& k) {
+  SurfPar q;
+  q.kind = k.surf.kind;
+  for (int j = 0; j < 5; ++j) q.p[j] = k.surf.par[j];
+  return q;
+}
+
+// f(x) and grad f(x): the signed distance of a sphere (|x - c| - r) or of a torus about the z
+// axis through c (sqrt((rho - R)^2 + (z - c_z)^2) - r, rho the distance from the axis)
+__device__ __forceinline__ double surf_eval(const SurfPar& q, const double* x, double* gr) {
+  const double d0 = x[0] - q.p[0], d1 = x[1] - q.p[1], d2 = x[2] - q.p[2];
+  if (q.kind == RC_SURFACE_SPHERE) {
+    const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    gr[0] = d0 / r;
+    gr[1] = d1 / r;
+    gr[2] = d2 / r;
+    return r - q.p[3];
+  }
+  const double rho = sqrt(d0 * d0 + d1 * d1);
+  const double a = rho - q.p[3];
+  const double qq = sqrt(a * a + d2 * d2);
+  gr[0] = a / qq * d0 / rho;
+  gr[1] = a / qq * d1 / rho;
+  gr[2] = d2 / qq;
+  return qq - q.p[4];
+}
+
+// grad f at the held vertices, and their unit normals in the per-vertex array
+__global__ void k_surface_prepare(const double* __restrict__ gamma, const int* __restrict__ sf, int nsf,
+                                  SurfPar q, double* __restrict__ sgrad, double* __restrict__ nrm) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nsf) return;
+  const int v = sf[j];
+  double gr[3];
+  surf_eval(q, gamma + 3 * (size_t)v, gr);
+  const double inv = 1.0 / sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+  for (int c = 0; c < 3; ++c) {
+    sgrad[3 * j + c] = gr[c];
+    nrm[3 * (size_t)v + c] = gr[c] * inv;
   }
 }
 
-// z_P = b_P (after z = F z)
-__global__ void k_pin_set(const double* __restrict__ b, int nbt, const int* __restrict__ pt, int npt,
-                          double* __restrict__ z) {
+// surface rows of Phi: f(gamma_i) from row0
+__global__ void k_phi_surface(const double* __restrict__ gamma, const int* __restrict__ sf, int nsf, SurfPar q,
+                              int row0, double* __restrict__ phi) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nsf) return;
+  double gr[3];
+  phi[row0 + j] = surf_eval(q, gamma + 3 * (size_t)sf[j], gr);
+}
+
+// surface rows of the dense C: grad f(gamma_i)^T at vertex i, from row0
+__global__ void k_dense_C_surface(const double* __restrict__ sgrad, const int* __restrict__ sf, int nsf, int row0,
+                                  int nV, double* __restrict__ Cd) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nsf) return;
+  for (int c = 0; c < 3; ++c) Cd[(size_t)(row0 + j) * 3 * nV + 3 * sf[j] + c] = sgrad[3 * j + c];
+}
+
+// The eliminated rows' part v of a particular solution of C z = b (z zero on entry): v_p = b_p at a
+// pinned vertex (its three point rows), v_i = b_i grad f / |grad f|^2 at a held vertex (its
+// surface row), so that those rows hold for v + F u whatever u.
+__global__ void k_particular(const double* __restrict__ b, int nbt, const int* __restrict__ pt, int npt,
+                             const int* __restrict__ sf, const double* __restrict__ sgrad, int nsf,
+                             double* __restrict__ z) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < 3 * npt) z[3 * (size_t)pt[i / 3] + i % 3] = b[nbt + i];
+  if (i < nsf) {
+    const double* gr = sgrad + 3 * i;
+    const double s = b[nbt + 3 * npt + i] / (gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+    for (int c = 0; c < 3; ++c) z[3 * (size_t)sf[i] + c] = s * gr[c];
+  }
 }
 
 __global__ void k_phi_border(const double* __restrict__ sm, int bary, int total, double total0,
@@ -233,12 +278,12 @@ __global__ void k_fill_pattern(double* __restrict__ x, int n, unsigned seed) {
 // constraints of one level
 // ---------------------------------------------------------------------------
 void cons_free(Cons& k) {
-  int* ip[] = {k.path_edge, k.path_prev, k.cut_edge, k.edge_path_row, k.pt};
+  int* ip[] = {k.path_edge, k.path_prev, k.cut_edge, k.edge_path_row, k.pt, k.sf};
   for (int* p : ip)
     if (p) hipFree(p);
   double* dp[] = {k.x0, k.len0, k.ones, k.geo, k.geo_eval, k.vals, k.rows, k.ta, k.td, k.tc, k.Kpb, k.Z, k.Sinv,
                   k.tri_scratch, k.wp, k.yp, k.wb, k.yb, k.dots, k.rhs, k.small, k.part, k.sp_VW, k.sp_Rt, k.sp_g,
-                  k.sp_U, k.sp_tmp, k.ptx, k.free, k.weff};
+                  k.sp_U, k.sp_tmp, k.ptx, k.free, k.weff, k.sgrad, k.nrm};
   for (double* p : dp)
     if (p) hipFree(p);
   if (k.prow) hipFree(k.prow);
@@ -247,12 +292,16 @@ void cons_free(Cons& k) {
   k = Cons();
 }
 
-rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const std::vector<int>& pts) {
+rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const std::vector<int>& pts,
+                     const SurfSpec* surf) {
   (void)c;
   cons_free(k);
   k.mask = mask;
   k.h_pt = pts;
   k.npt = (int)pts.size();
+  if (surf && surf->kind && !surf->verts.empty()) k.surf = *surf;
+  k.nsf = (int)k.surf.verts.size();
+  k.elim = k.npt > 0 || k.nsf > 0;
   k.bary = (mask & RC_C_BARYCENTER) ? 1 : 0;
   k.total = (mask & RC_C_TOTAL_LENGTH) ? 1 : 0;
   k.edge = (mask & RC_C_EDGE_LENGTH) ? 1 : 0;
@@ -287,7 +336,7 @@ rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const s
   k.np = (int)k.h_path_edge.size();
   k.ncut = (int)k.h_cut_edge.size();
   k.nbt = 3 * k.bary + k.total;
-  k.nd = k.nbt + 3 * k.npt;
+  k.nd = k.nbt + 3 * k.npt + k.nsf;
   k.nb = k.nbt + k.ncut;
   k.k = k.nd + (k.edge ? nE : 0);
   if (k.nb > 120) {
@@ -295,16 +344,25 @@ rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const s
               "for barycenter and total length, 1 per loop and 1 per edge at a vertex of degree >= 3)");
     return RC_ERR_UNSUPPORTED;
   }
-  if (k.npt) {
-    RC_TRY(dalloc(&k.pt, k.npt));
-    RC_TRY(dalloc(&k.ptx, 3 * (size_t)k.npt));
+  if (k.elim) {
     RC_TRY(dalloc(&k.free, nV));
     RC_TRY(dalloc(&k.weff, nV));
     std::vector<double> fr(nV, 1.0);
     for (int v : pts) fr[v] = 0.0;
+    RC_HIP(hipMemcpy(k.free, fr.data(), sizeof(double) * nV, hipMemcpyHostToDevice));
+  }
+  if (k.npt) {
+    RC_TRY(dalloc(&k.pt, k.npt));
+    RC_TRY(dalloc(&k.ptx, 3 * (size_t)k.npt));
     RC_HIP(hipMemcpy(k.pt, pts.data(), sizeof(int) * k.npt, hipMemcpyHostToDevice));
     RC_HIP(hipMemset(k.ptx, 0, sizeof(double) * 3 * k.npt));
-    RC_HIP(hipMemcpy(k.free, fr.data(), sizeof(double) * nV, hipMemcpyHostToDevice));
+  }
+  if (k.nsf) {
+    RC_TRY(dalloc(&k.sf, k.nsf));
+    RC_TRY(dalloc(&k.sgrad, 3 * (size_t)k.nsf));
+    RC_TRY(dalloc(&k.nrm, 3 * (size_t)nV));
+    RC_HIP(hipMemcpy(k.sf, k.surf.verts.data(), sizeof(int) * k.nsf, hipMemcpyHostToDevice));
+    RC_HIP(hipMemset(k.nrm, 0, sizeof(double) * 3 * nV));
   }
   RC_TRY(dalloc(&k.path_edge, k.np));
   RC_TRY(dalloc(&k.path_prev, k.np));
@@ -402,10 +460,13 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma,
   if (k.k == 0) return RC_OK;
   hipStream_t s = c->stream;
   const int nV = cv.nV, nE = cv.nE;
-  if (k.npt) {
+  if (k.elim) {
     free_weights(w, k.free, nV, k.weff, s);
     w = k.weff;
   }
+  if (k.nsf)
+    hipLaunchKernelGGL(k_surface_prepare, dim3(cdiv(k.nsf, 64)), dim3(64), 0, s, gamma, k.sf, k.nsf, surf_par(k),
+                       k.sgrad, k.nrm);
   cons_geometry(gamma, cv.edges, nE, k.geo, s);
   cons_border_rows(k.geo, cv.inc_off, cv.inc, cv.edges, k.x0, nV, k.bary, k.total, k.cut_edge, k.ncut, k.rows,
                    k.nb, s);
@@ -414,7 +475,7 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma,
   double* uinv = k.tri_scratch + np;
   int* tinfo = (int*)(k.tri_scratch + 2 * np);
   if (np > 0) {
-    cons_path_coeffs(k.geo, cv.edges, k.path_edge, k.path_prev, np, w, k.ta, k.td, k.tc, s);
+    cons_path_coeffs(k.geo, cv.edges, k.path_edge, k.path_prev, np, w, k.nrm, k.ta, k.td, k.tc, s);
     tri_prepare(k.ta, k.td, k.tc, k.tri, lo, uinv, k.sp_VW, k.sp_Rt, k.sp_tmp, tinfo, s);
     int info = 0;
     RC_HIP(hipMemcpyAsync(&info, tinfo, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -430,7 +491,7 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma,
     const double* rows2 = k.rows;  // W rows
     if (w) {
       if (!k.rowsW) RC_TRY(dalloc(&k.rowsW, (size_t)nb * 3 * nV));
-      cons_scale_rows(k.rows, w, nV, nb, k.rowsW, s);
+      cons_scale_rows(k.rows, w, k.nrm, nV, nb, k.rowsW, s);
       rows2 = k.rowsW;
     }
     for (int r = 0; r < nb; ++r)
@@ -446,7 +507,7 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma,
     for (int i = 0; i < nb * nb; ++i) S[i] -= kz[i];
     // a border row that vanishes on the free vertices (a cut edge with both ends pinned) is zero
     // in S: a unit diagonal gives it a zero multiplier
-    if (k.npt)
+    if (k.elim)
       for (int i = 0; i < nb; ++i)
         if (S[i * nb + i] == 0.0) S[i * nb + i] = 1.0;
     if (!invert_small(S, nb)) {
@@ -519,7 +580,8 @@ static void cons_project_w(rc_ctx* c, const Curve& cv, Cons& kw, const double* w
                            bool xset = false, const LowpOp* pop = nullptr, bool pfrom_x = false) {
   ProjData d = proj_data(cv, kw);
   set_prep(d, pop, pfrom_x);
-  d.w = kw.npt ? kw.weff : w;  // (w times the free mask with pinned vertices, as prepared)
+  d.w = kw.elim ? kw.weff : w;  // (w times the free mask with pinned vertices, as prepared)
+  d.nrm = kw.nrm;
   d.scale = scale;
   d.beta = beta;
   d.prev = prev;
@@ -529,9 +591,10 @@ static void cons_project_w(rc_ctx* c, const Curve& cv, Cons& kw, const double* w
 }
 
 // out = P in with P = I - C^T (C C^T)^-1 C (in may equal out), the orthogonal
-// projector onto null(C); with pinned vertices P = F - F C^T (C F C^T)^-1 C F
-// (F the free mask), onto null(C) with the pinned entries zero.  With xacc,
-// also xacc += out.
+// projector onto null(C); with pinned vertices and surface constraints
+// P = F - F C^T (C F C^T)^-1 C F (F_v = 0 at a pinned vertex, I - n_v n_v^T on
+// a surface, I elsewhere), onto null(C) with the pinned entries zero and the
+// held vertices' entries tangent to the surface.  With xacc, also xacc += out.
 bool cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double* out, double* xacc,
                   const LowpOp* pop, bool pfrom_x) {
   hipStream_t s = c->stream;
@@ -543,51 +606,63 @@ bool cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double*
   }
   if (k.nb <= kProjMaxBorder) {
     ProjData d = proj_data(cv, k);
-    d.w = k.npt ? k.weff : nullptr;
+    d.w = k.elim ? k.weff : nullptr;
+    d.nrm = k.nrm;
     d.xacc = xacc;
     set_prep(d, pop, pfrom_x);
     cons_project_fused(d, in, out, s);
     return pop != nullptr;
   }
-  if (k.npt) {  // F in, then F (F in - C^T y) with y from C F in
+  if (k.elim) {  // F in, then F (F in - C^T y) with y from C F in
     if (in != out) vec_copy(in, out, 3 * nV, s);
-    mask_vertices(out, k.free, nV, s);
+    mask_vertices(out, k.weff, k.nrm, nV, s);
     in = out;
   }
   cons_path_apply(k.geo, cv.edges, k.path_edge, k.np, in, nV, 1, k.wp, s);
   if (k.nb > 0) vec_dots(k.rows, 3 * nV, in, 0, 3 * nV, k.nb, c->red, k.wb, s);
   cons_solve_K(c, k);
   cons_apply_CT(k.geo, cv.inc_off, cv.inc, k.edge_path_row, k.yp, k.rows, k.yb, k.nb, nV, in, out, s);
-  if (k.npt) mask_vertices(out, k.free, nV, s);
+  if (k.elim) mask_vertices(out, k.weff, k.nrm, nV, s);
   if (xacc) vec_axpby(1.0, out, 1.0, xacc, 3 * nV, s);
   return false;
 }
 
 // A particular solution z of C z = b for an external-order b (finest level):
-// z = C^T (C C^T)^-1 b, the minimum-norm one, without pinned vertices; with
-// them z_P = b_P and z_F = F C^T (C F C^T)^-1 (b_C - C v_P) (v_P the point
-// rows of b at their vertices), which satisfies every row.
-static void cons_min_norm(rc_ctx* c, const double* b, double* z) {
+// z = C^T (C C^T)^-1 b, the minimum-norm one, without eliminated rows; with
+// point and surface rows z = v + F C^T (C F C^T)^-1 (b_C - C v), v their part
+// (k_particular), which satisfies every row.  scratch: [3 nV].
+static void cons_min_norm(rc_ctx* c, const double* b, double* z, double* scratch) {
   Cons& k = c->cons;
   hipStream_t s = c->stream;
-  const int nV = c->nV;
+  const int nV = c->nV, n3 = 3 * nV;
   const int n = std::max(k.np, std::max(k.nb, 1));
   hipLaunchKernelGGL(k_map_rhs, dim3(cdiv(n, 256)), dim3(256), 0, s, b, k.nbt, k.nd, k.path_edge, k.np,
                      k.cut_edge, k.ncut, k.wp, k.wb, -1.0);
-  if (k.npt)
-    hipLaunchKernelGGL(k_pin_rhs, dim3(1), dim3(1), 0, s, b, k.nbt, k.pt, k.npt, k.rows, k.nb, nV, k.geo,
-                       c->curve.inc_off, c->curve.inc, k.edge_path_row, k.wp, k.wb, -1.0);
+  if (k.elim) {  // (wp, wb) = -(b_C - C v)
+    hipLaunchKernelGGL(k_fill, dim3(cdiv(n3, 256)), dim3(256), 0, s, z, n3, 0.0);
+    hipLaunchKernelGGL(k_particular, dim3(cdiv(std::max(3 * k.npt, k.nsf), 64)), dim3(64), 0, s, b, k.nbt, k.pt,
+                       k.npt, k.sf, k.sgrad, k.nsf, z);
+    if (k.np > 0) {
+      cons_path_apply(k.geo, c->curve.edges, k.path_edge, k.np, z, nV, 1, k.yp, s);
+      vec_axpby(1.0, k.yp, 1.0, k.wp, k.np, s);
+    }
+    if (k.nb > 0) {
+      vec_dots(k.rows, n3, z, 0, n3, k.nb, c->red, k.yb, s);
+      vec_axpby(1.0, k.yb, 1.0, k.wb, k.nb, s);
+    }
+  }
   cons_solve_K(c, k);
   // apply_CT computes in - C^T y with in = null: -C^T y, and y = K^-1 (-b)
-  cons_apply_CT(k.geo, c->curve.inc_off, c->curve.inc, k.edge_path_row, k.yp, k.rows, k.yb, k.nb, nV, nullptr, z,
+  double* u = k.elim ? scratch : z;
+  cons_apply_CT(k.geo, c->curve.inc_off, c->curve.inc, k.edge_path_row, k.yp, k.rows, k.yb, k.nb, nV, nullptr, u,
                 s);
-  if (k.npt) {
-    mask_vertices(z, k.free, nV, s);
-    hipLaunchKernelGGL(k_pin_set, dim3(cdiv(3 * k.npt, 64)), dim3(64), 0, s, b, k.nbt, k.pt, k.npt, z);
+  if (k.elim) {
+    mask_vertices(u, k.weff, k.nrm, nV, s);
+    vec_axpby(1.0, u, 1.0, z, n3, s);
   }
 }
 
-// Phi(gamma) in external order (barycenter, total length, points, edges).
+// Phi(gamma) in external order (barycenter, total length, points, surface, edges).
 void cons_values(rc_ctx* c, const double* gamma, double* phi) {
   Cons& k = c->cons;
   hipStream_t s = c->stream;
@@ -601,6 +676,9 @@ void cons_values(rc_ctx* c, const double* gamma, double* phi) {
   }
   if (k.npt > 0)
     hipLaunchKernelGGL(k_phi_points, dim3(cdiv(3 * k.npt, 64)), dim3(64), 0, s, gamma, k.pt, k.ptx, k.npt, nbt, phi);
+  if (k.nsf > 0)
+    hipLaunchKernelGGL(k_phi_surface, dim3(cdiv(k.nsf, 64)), dim3(64), 0, s, gamma, k.sf, k.nsf, surf_par(k),
+                       nbt + 3 * k.npt, phi);
 }
 
 // ---------------------------------------------------------------------------
@@ -655,11 +733,14 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
   RC_TRY(launch_assemble_dense(cv, c->alpha, c->beta, d.A, s));
   if (kk > 0) {
     // dense C in external order: the border rows of barycenter and total length, the point
-    // rows, then the edge rows
+    // rows, the surface rows, then the edge rows
     RC_HIP(hipMemsetAsync(d.Cd, 0, sizeof(double) * (size_t)kk * n, s));
     if (k.nbt > 0)
       RC_HIP(hipMemcpyAsync(d.Cd, k.rows, sizeof(double) * (size_t)k.nbt * n, hipMemcpyDeviceToDevice, s));
     dense_C_points(k.pt, k.npt, k.nbt, nV, d.Cd, s);
+    if (k.nsf)
+      hipLaunchKernelGGL(k_dense_C_surface, dim3(cdiv(k.nsf, 64)), dim3(64), 0, s, k.sgrad, k.sf, k.nsf,
+                         k.nbt + 3 * k.npt, nV, d.Cd);
     if (k.edge) dense_C_edges(k.geo, cv.edges, cv.nE, k.nd, nV, k.free, d.Cd, s);
     dense_gemm(d.Cd, d.Cd, d.CtC, n, n, kk, 0.0, true, s);
   } else {
@@ -678,7 +759,7 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
   if (kk > 0) {
     dense_gemm(d.X, d.Cd, d.W, n, kk, n, 0.0, false, s, true);  // W = H^-1 C^T
     dense_gemm(d.Cd, d.W, d.Sinv, kk, kk, n, 0.0, false, s);    // S = C H^-1 C^T (SPD)
-    if (k.npt) unit_zero_diag(d.Sinv, kk, s);  // the zero rows of edges with both ends pinned
+    if (k.elim) unit_zero_diag(d.Sinv, kk, s);  // the zero rows of edges with both ends pinned
     gj_invert_spd(d.Sinv, kk, d.gjm, d.gjo, d.gjc, d.info + 1, s);
     // X += (-W S^-1) W^T, with -W S^-1 staged in CtC (no longer needed)
     dense_gemm(d.W, d.Sinv, d.CtC, n, kk, kk, 0.0, false, s);
@@ -772,6 +853,7 @@ static rc_status mg_build(rc_ctx* c) {
   c->levels.emplace_back(nullptr);
   const Curve* fine = &c->curve;
   std::vector<int> fine_pts = c->cons.h_pt;
+  SurfSpec fine_surf = c->cons.surf;
   while (fine->nV > c->mg_min) {
     std::vector<Chain> chs = chains_of(*fine);
     // black/white coarsening: keep even chain positions, and both ends of open paths
@@ -837,8 +919,14 @@ static rc_status mg_build(rc_ctx* c) {
     RC_HIP(hipMemcpy(L->restr_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice));
     // the level's own constraints (same kinds as the finest level); a pinned vertex pins the
     // coarse vertices it interpolates from, so that every prolonged correction vanishes on it
-    RC_TRY(cons_alloc(c, L->curve, L->cons, c->cons.mask, coarse_pts));
+    // a held vertex that the coarsening keeps stays on the surface
+    SurfSpec csurf = fine_surf;
+    csurf.verts.clear();
+    for (int v : fine_surf.verts)
+      if (coarse_id[v] >= 0) csurf.verts.push_back(coarse_id[v]);
+    RC_TRY(cons_alloc(c, L->curve, L->cons, c->cons.mask, coarse_pts, &csurf));
     fine_pts = coarse_pts;
+    fine_surf = csurf;
     if (c->cons.bary)
       RC_HIP(hipMemcpy(L->cons.x0, c->cons.x0, sizeof(double) * 3, hipMemcpyDeviceToDevice));
     c->levels.push_back(std::move(L));
@@ -941,7 +1029,8 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
     const int n = cv.nV;
     if (c->mg_weighted) {  // factors of C W C^T, W = D^-1
       Cons& Kw = level_cons_w(c, l);
-      if (Kw.mask != K.mask || Kw.h_pt != K.h_pt || !Kw.geo) RC_TRY(cons_alloc(c, cv, Kw, K.mask, K.h_pt));
+      if (Kw.mask != K.mask || Kw.h_pt != K.h_pt || Kw.surf != K.surf || !Kw.geo)
+        RC_TRY(cons_alloc(c, cv, Kw, K.mask, K.h_pt, &K.surf));
       RC_HIP(hipMemcpyAsync(Kw.x0, K.x0, sizeof(double) * 3, hipMemcpyDeviceToDevice, s));
       hipLaunchKernelGGL(k_recip, dim3(cdiv(n, 256)), dim3(256), 0, s, st.diag, n, st.w);
       RC_TRY(cons_prepare(c, cv, Kw, l == 0 ? gamma : c->levels[l]->gamma, st.w));
@@ -1552,7 +1641,7 @@ static rc_status projection_increment(rc_ctx* c, const double* phi, double* x, c
     return RC_OK;
   }
   hipLaunchKernelGGL(k_negate, dim3(cdiv(k, 256)), dim3(256), 0, s, phi, c->phi + k, k);
-  cons_min_norm(c, c->phi + k, c->zmin);
+  cons_min_norm(c, c->phi + k, c->zmin, c->inc);
   if (o.lowp_outer == 2 && c->lowp_levels > 0) RC_TRY(launch_lowp_apply(c->lowp, c->zmin, c->inc, s, nullptr));
   else RC_TRY(apply_A(c, c->curve, c->zmin, c->inc, o.op_f64 ? RC_F64 : c->dtype));
   double res = 0.0;
