@@ -21,16 +21,25 @@ Definitions (paper Sec. 7.1 "Constraints and Potentials"):
   of length): a sphere ``f = |x - c| - r`` and a torus about the axis through c
   along z, ``f = sqrt((rho - R)^2 + (z - c_z)^2) - r`` with rho the distance
   from that axis.
+* Tangent: the paper writes ``Phi_{tangent,I} = T_I - X`` (3 rows), whose
+  Jacobian has rank 2 only (T_I stays a unit vector).  Read here as the two
+  independent rows ``(u . T_I, v . T_I)`` with (u, v) an orthonormal basis of
+  the plane orthogonal to the unit direction X: ``u = (X x e_m) / |X x e_m|``
+  with e_m the coordinate axis of the smallest |X_m| (the first on ties) and
+  ``v = X x u``.  They vanish exactly when T_I is parallel to X (the branch
+  T_I . X > 0 is the one a step from near X stays on).  Jacobian of u . T_I:
+  ``(u - (u . T_I) T_I) / l_I`` at i2 and its negative at i1.
 * Loop length: the total-length constraint applied to every connected
   component (closed loop) separately, ``Phi_q = L0_q - sum_{I in q} l_I``
   (one row per component, components ordered by their smallest vertex), as a
   packing of several curves keeps each curve's length.
 
-Rows are stacked in the order barycenter, total length, points, surface, edge
-lengths, loop lengths.  Points are passed as ``points=(vertices, targets)`` and
-surfaces as ``surface=(kind, params, vertices)`` (kind SPHERE with params
-(c_x, c_y, c_z, r), or TORUS with (c_x, c_y, c_z, R, r)) beside the flags (no
-flag of their own: an empty vertex list is no such constraint).
+Rows are stacked in the order barycenter, total length, points, surface,
+tangents, edge lengths, loop lengths.  Points are passed as
+``points=(vertices, targets)``, surfaces as ``surface=(kind, params,
+vertices)`` (kind SPHERE with params (c_x, c_y, c_z, r), or TORUS with
+(c_x, c_y, c_z, R, r)) and tangents as ``tangent=(edges, directions)`` beside
+the flags (no flag of their own: an empty list is no such constraint).
 Vectors in R^{3|V|} are vertex-major: entry ``3 v + c`` is coordinate c of
 vertex v.
 """
@@ -42,7 +51,7 @@ import numpy as np
 from .tpe import edge_geometry
 
 __all__ = ["BARYCENTER", "TOTAL_LENGTH", "EDGE_LENGTH", "LOOP_LENGTH", "SPHERE", "TORUS", "reference_values",
-           "components", "loop_lengths", "surface_value", "evaluate", "jacobian_sparse"]
+           "components", "loop_lengths", "surface_value", "tangent_basis", "evaluate", "jacobian_sparse"]
 
 BARYCENTER = 1
 TOTAL_LENGTH = 2
@@ -67,6 +76,20 @@ def surface_value(kind, params, x):
         grad = np.stack([a / q * d[:, 0] / rho, a / q * d[:, 1] / rho, d[:, 2] / q], axis=1)
         return q - p[4], grad
     raise ValueError("unknown surface kind")
+
+
+def tangent_basis(X):
+    """(u, v): the orthonormal basis of the plane orthogonal to the unit vector X
+    used by the tangent rows (u = X x e_m / |X x e_m|, e_m the axis of the
+    smallest |X_m|, first on ties; v = X x u)."""
+    X = np.asarray(X, dtype=np.float64)
+    X = X / np.linalg.norm(X)
+    m = int(np.argmin(np.abs(X)))
+    em = np.zeros(3)
+    em[m] = 1.0
+    u = np.cross(X, em)
+    u /= np.linalg.norm(u)
+    return u, np.cross(X, u)
 
 
 def reference_values(gamma, edges):
@@ -105,11 +128,13 @@ def loop_lengths(gamma, edges):
     return np.bincount(comp, weights=ell)
 
 
-def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True, Lq=None, points=None, surface=None):
+def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True, Lq=None, points=None, surface=None,
+             tangent=None):
     """(Phi, C) for the constraint set ``mask`` (bitwise OR of the flags);
     ``Lq`` are the loop-length targets, ``points`` = (vertices, targets [m][3])
     the pinned vertices, ``surface`` = (kind, params, vertices) the vertices
-    held on an implicit surface."""
+    held on an implicit surface, ``tangent`` = (edges, directions [m][3]) the
+    edges whose tangent is prescribed."""
     g = np.asarray(gamma, dtype=np.float64)
     e = np.asarray(edges)
     nV, nE = len(g), len(e)
@@ -150,6 +175,20 @@ def evaluate(gamma, edges, mask, x0=None, L0=None, l0=None, jacobian=True, Lq=No
             for j, v in enumerate(sv):
                 Cs[j, 3 * v:3 * v + 3] = grad[j]
             jacs.append(Cs)
+    if tangent is not None and len(tangent[0]):
+        te = np.asarray(tangent[0], dtype=np.int64)
+        X = np.asarray(tangent[1], dtype=np.float64).reshape(len(te), 3)
+        Ct = np.zeros((2 * len(te), 3 * nV))
+        ph = []
+        for j, I in enumerate(te):
+            for k, b in enumerate(tangent_basis(X[j])):
+                ph.append(b @ T[I])
+                r = (b - (b @ T[I]) * T[I]) / ell[I]
+                Ct[2 * j + k, 3 * e[I, 1]:3 * e[I, 1] + 3] += r
+                Ct[2 * j + k, 3 * e[I, 0]:3 * e[I, 0] + 3] -= r
+        phis.append(np.array(ph))
+        if jacobian:
+            jacs.append(Ct)
     if mask & EDGE_LENGTH:
         phis.append(l0 - ell)
         if jacobian:

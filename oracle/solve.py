@@ -165,8 +165,9 @@ def projection_increment_transform(A, C, phi):
     return (z - y.ravel()).reshape(-1, 3)
 
 
-def _phi_tolerance(gamma, edges, mask, n_points=0, n_surface=0):
+def _phi_tolerance(gamma, edges, mask, n_points=0, n_surface=0, n_tangent=0):
     """Per-row projection tolerance: 1e-10 l_mean (edge lengths, points, surface),
+    1e-10 (the dimensionless tangent rows),
     1e-10 L l_mean (barycenter), 1e-10 L (total length) and 1e-10 L_q (length
     of loop q)."""
     ell, _, _ = tpe.edge_geometry(gamma, edges)
@@ -177,6 +178,7 @@ def _phi_tolerance(gamma, edges, mask, n_points=0, n_surface=0):
     if mask & cons.TOTAL_LENGTH:
         tol += [1e-10 * L]
     tol += [1e-10 * lbar] * (3 * n_points + n_surface)
+    tol += [1e-10] * (2 * n_tangent)
     if mask & cons.EDGE_LENGTH:
         tol += [1e-10 * lbar] * len(edges)
     if mask & cons.LOOP_LENGTH:
@@ -184,21 +186,24 @@ def _phi_tolerance(gamma, edges, mask, n_points=0, n_surface=0):
     return np.array(tol)
 
 
-def project(gamma_t, edges, A, C, mask, refs, max_iter=10, tol=None, points=None, surface=None):
+def project(gamma_t, edges, A, C, mask, refs, max_iter=10, tol=None, points=None, surface=None, tangent=None):
     """Iterate the projection increment from gamma_t; returns (gamma, iters, ok).
 
     ``refs`` is ``(x0, L0, l0)`` or ``(x0, L0, l0, Lq)`` with the loop-length
     targets ``Lq`` (needed when ``mask`` has LOOP_LENGTH); ``points`` =
     (vertices, targets) of the point constraints, ``surface`` = (kind,
-    params, vertices) of the surface constraints."""
+    params, vertices) of the surface constraints, ``tangent`` = (edges,
+    directions) of the tangent constraints."""
     x0, L0, l0 = refs[:3]
     Lq = refs[3] if len(refs) > 3 else None
     g = np.array(gamma_t, dtype=np.float64)
     npt = 0 if points is None else len(points[0])
     nsf = 0 if surface is None else len(surface[2])
-    tol = _phi_tolerance(g, edges, mask, npt, nsf) if tol is None else tol
+    ntg = 0 if tangent is None else len(tangent[0])
+    tol = _phi_tolerance(g, edges, mask, npt, nsf, ntg) if tol is None else tol
     for it in range(max_iter + 1):
-        phi, _ = cons.evaluate(g, edges, mask, x0, L0, l0, jacobian=False, Lq=Lq, points=points, surface=surface)
+        phi, _ = cons.evaluate(g, edges, mask, x0, L0, l0, jacobian=False, Lq=Lq, points=points, surface=surface,
+                               tangent=tangent)
         if np.all(np.abs(phi) <= tol):
             return g, it, True
         if it == max_iter:
@@ -208,14 +213,14 @@ def project(gamma_t, edges, A, C, mask, refs, max_iter=10, tol=None, points=None
 
 
 def line_search(gamma, edges, alpha, beta, E0, dE, g_tilde, A, C, mask, refs,
-                c_armijo=0.01, shrink=0.5, max_backtracks=30, tau0=1.0, points=None, surface=None):
+                c_armijo=0.01, shrink=0.5, max_backtracks=30, tau0=1.0, points=None, surface=None, tangent=None):
     """Backtracking step of Sec. 4.4; returns (gamma_new, tau, E_new, info)."""
     ghat = g_tilde / np.linalg.norm(g_tilde)
     slope = float(np.sum(dE * ghat))
     tau = tau0
     for bt in range(max_backtracks + 1):
         cand = gamma - tau * ghat
-        proj, iters, ok = project(cand, edges, A, C, mask, refs, points=points, surface=surface)
+        proj, iters, ok = project(cand, edges, A, C, mask, refs, points=points, surface=surface, tangent=tangent)
         if ok:
             E1 = tpe.energy(proj, edges, alpha, beta)
             if E1 <= E0 - c_armijo * tau * slope:
@@ -224,16 +229,16 @@ def line_search(gamma, edges, alpha, beta, E0, dE, g_tilde, A, C, mask, refs,
     return gamma, 0.0, E0, dict(backtracks=max_backtracks, proj_iters=0, ok=False)
 
 
-def step(gamma, edges, alpha, beta, mask, refs, points=None, surface=None):
+def step(gamma, edges, alpha, beta, mask, refs, points=None, surface=None, tangent=None):
     """One projected Sobolev step: dE, A, C, g_tilde, line search."""
     E0, dE = tpe.differential(gamma, edges, alpha, beta)
     B, B0 = sobolev.assemble(gamma, edges, alpha, beta)
     A = B + B0
     x0, L0, l0 = refs[:3]
     _, C = cons.evaluate(gamma, edges, mask, x0, L0, l0, Lq=refs[3] if len(refs) > 3 else None, points=points,
-                         surface=surface)
+                         surface=surface, tangent=tangent)
     g, _ = projected_gradient(A, C, dE)
     new, tau, E1, info = line_search(gamma, edges, alpha, beta, E0, dE, g, A, C, mask, refs, points=points,
-                                     surface=surface)
+                                     surface=surface, tangent=tangent)
     info.update(E0=E0, E1=E1, tau=tau, g=g, dE=dE)
     return new, info

@@ -335,3 +335,70 @@ def test_surface_jacobian_gradient_and_step(kind):
     assert info["ok"] and info["E1"] < info["E0"]
     f, _ = cons.surface_value(surf[0], surf[1], new[surf[2]])
     assert np.abs(f).max() <= 1e-10 * refs[2].mean()
+
+
+# --- tangent constraints (Sec. 7.1) -----------------------------------------
+
+
+def test_tangent_basis_rule():
+    u, v = cons.tangent_basis([0.0, 0.0, 2.0])
+    assert np.allclose(u, [0, 1, 0], atol=0) and np.allclose(v, [-1, 0, 0], atol=0)
+    for X in np.random.default_rng(4).normal(size=(5, 3)):
+        u, v = cons.tangent_basis(X)
+        Xn = X / np.linalg.norm(X)
+        B = np.stack([u, v, Xn])
+        assert np.allclose(B @ B.T, np.eye(3), atol=1e-14)
+        assert np.allclose(np.cross(u, v), Xn, atol=1e-14)
+
+
+def test_tangent_rows_values_jacobian_and_paper_form():
+    g, e = gen.trefoil(40, seed=21)
+    ell, T, _ = tpe.edge_geometry(g, e)
+    I = 7
+    X = T[I].copy()
+    # the rows vanish at T_I = X; turning X by theta about u's orthogonal gives u . T = sin(theta)
+    phi, C = cons.evaluate(g, e, 0, tangent=([I], [X]))
+    assert np.abs(phi).max() < 1e-15
+    u, v = cons.tangent_basis(X)
+    th = 0.3
+    Xr = np.cos(th) * X - np.sin(th) * u  # then T_I = cos(th) Xr + sin(th) u', u' . T_I = sin(th)
+    phi_r, _ = cons.evaluate(g, e, 0, tangent=([I], [Xr]))
+    ur, vr = cons.tangent_basis(Xr)
+    assert np.allclose(phi_r, [ur @ T[I], vr @ T[I]], atol=1e-15)
+    assert np.hypot(*phi_r) == pytest.approx(np.sin(th), rel=1e-12)
+    # Jacobian against central differences, with another tangent and the barycenter rows
+    tg = ([I, 20], [Xr, T[20] + 0.1])
+    refs = cons.reference_values(g, e)
+    _, C = cons.evaluate(g, e, cons.BARYCENTER, *refs, tangent=tg)
+    h = 1e-6
+    for vtx, c in [(7, 0), (8, 2), (20, 1), (21, 0), (3, 1)]:
+        gp, gm = g.copy(), g.copy()
+        gp[vtx, c] += h
+        gm[vtx, c] -= h
+        fd = (cons.evaluate(gp, e, cons.BARYCENTER, *refs, jacobian=False, tangent=tg)[0]
+              - cons.evaluate(gm, e, cons.BARYCENTER, *refs, jacobian=False, tangent=tg)[0]) / (2 * h)
+        assert np.allclose(C[:, 3 * vtx + c], fd, rtol=1e-7, atol=1e-8)
+    # the paper's three rows T_I - X: their Jacobian (by differences of T_I) has rank 2 and the
+    # same row space as the two rows read here
+    J3 = np.zeros((3, 3 * len(g)))
+    for vtx in e[I]:
+        for c in range(3):
+            gp, gm = g.copy(), g.copy()
+            gp[vtx, c] += h
+            gm[vtx, c] -= h
+            J3[:, 3 * vtx + c] = (tpe.edge_geometry(gp, e)[1][I] - tpe.edge_geometry(gm, e)[1][I]) / (2 * h)
+    _, C2 = cons.evaluate(g, e, 0, tangent=([I], [X]))
+    assert np.linalg.matrix_rank(J3, tol=1e-6) == 2
+    assert np.linalg.matrix_rank(np.vstack([J3, C2]), tol=1e-6) == 2
+
+
+def test_tangent_constrained_step_keeps_tangents():
+    g, e = gen.trefoil(48, seed=21)
+    _, T, _ = tpe.edge_geometry(g, e)
+    tg = ([0, 24], [T[0], T[24]])
+    refs = cons.reference_values(g, e)
+    new, info = solve.step(g, e, 2.0, 4.5, cons.BARYCENTER | cons.EDGE_LENGTH, refs, tangent=tg)
+    assert info["ok"] and info["E1"] < info["E0"]
+    _, T1, _ = tpe.edge_geometry(new, e)
+    assert np.abs(T1[[0, 24]] - T[[0, 24]]).max() < 1e-9
+    assert np.abs(new - g).max() > 1e-4
