@@ -343,10 +343,30 @@ enum { RC_SURFACE_SPHERE = 1, RC_SURFACE_TORUS = 2 };
 rc_status rc_set_surface_constraints(rc_ctx* ctx, int32_t kind, const double* params_h, int32_t n,
                                      const int32_t* vertices_h);
 
+/* Tangent constraints (Sec. 7.1): the unit tangent T_I of each listed edge
+ * is held parallel to a direction X.  The printed rows T_I - X have a rank-2
+ * Jacobian (T_I stays a unit vector), so the constraint is taken as the two
+ * independent rows (u . T_I, v . T_I), (u, v) the orthonormal basis of the
+ * plane orthogonal to X/|X| with u = X x e_m / |X x e_m| (e_m the coordinate
+ * axis of the smallest |X_m|, the first on ties) and v = X x u; they vanish
+ * exactly when T_I is parallel to X, and a step from near X stays on that
+ * branch.  Jacobian of b . T_I: (b - (b . T_I) T_I) / l_I at i2, its negative
+ * at i1; the rows are dimensionless, so the step's projection tolerance for
+ * them is proj_tol itself.  edges_h: HOST int32 [n], distinct edge indices;
+ * dirs_h: HOST double [n][3], nonzero directions X.  n in [0, nE]; 0 removes
+ * them.  Each adds two rows to the projector's small dense block (the fused
+ * projector serves up to 8 such rows with barycenter, total length and loop
+ * cuts); the coarser multigrid levels do not carry them (the V-cycle projects
+ * every prolonged correction onto the finest level's constraints).  Errors:
+ * RC_ERR_ARG (n out of range, null pointers, an edge out of range or given
+ * twice, a zero or non-finite direction), RC_ERR_UNSUPPORTED (more than 120
+ * rows in the dense block). */
+rc_status rc_set_tangent_constraints(rc_ctx* ctx, int32_t n, const int32_t* edges_h, const double* dirs_h);
+
 /* Phi(gamma) (Sec. 7.1) in the row order barycenter (3), total length (1),
  * points (3 each, in the order given), surface (1 per held vertex, in the
- * order given), edge lengths (nE), restricted to the active set.  phi:
- * device double [k]. */
+ * order given), tangents (2 each, in the order given), edge lengths (nE),
+ * restricted to the active set.  phi: device double [k]. */
 rc_status rc_constraint_values(rc_ctx* ctx, const double* gamma, double* phi);
 
 /* Number of active constraint rows k. */

@@ -30,7 +30,8 @@ STATUS = {
 EXPORTED = [
     "rc_default_solve_opts", "rc_default_ls_opts", "rc_last_error", "rc_create", "rc_destroy", "rc_energy",
     "rc_differential", "rc_sobolev_apply", "rc_sobolev_apply_prec", "rc_sobolev_diag", "rc_assemble_dense",
-    "rc_set_constraints", "rc_set_point_constraints", "rc_set_surface_constraints", "rc_constraint_values",
+    "rc_set_constraints", "rc_set_point_constraints", "rc_set_surface_constraints", "rc_set_tangent_constraints",
+    "rc_constraint_values",
     "rc_constraint_count", "rc_project",
     "rc_sobolev_gradient",
     "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_bh_last_work", "rc_midpoint_differential",
@@ -116,6 +117,7 @@ def load():
         "rc_set_constraints": (I32, [P, U32, P, P, D, P]),
         "rc_set_point_constraints": (I32, [P, I32, P, P]),
         "rc_set_surface_constraints": (I32, [P, I32, P, I32, P]),
+        "rc_set_tangent_constraints": (I32, [P, I32, P, P]),
         "rc_constraint_values": (I32, [P, P, P]),
         "rc_constraint_count": (I32, [P]),
         "rc_project": (I32, [P, P, P, P]),
@@ -337,6 +339,17 @@ class Context:
         self._sp = (C.c_double * max(len(p), 5))(*p)
         _check(load().rc_set_surface_constraints(self.h, int(kind), C.cast(self._sp, C.c_void_p), len(v),
                                                  C.cast(self._sv, C.c_void_p)))
+
+    def rc_set_tangent_constraints(self, edges=(), directions=()):
+        """Hold the unit tangent of edges[j] parallel to directions[j]."""
+        ed = [int(i) for i in edges]
+        d = [float(x) for row in directions for x in row]
+        if len(d) != 3 * len(ed):
+            raise ValueError("directions must hold three coordinates per edge")
+        self._te = (C.c_int32 * max(len(ed), 1))(*ed)
+        self._td = (C.c_double * max(len(d), 1))(*d)
+        _check(load().rc_set_tangent_constraints(self.h, len(ed), C.cast(self._te, C.c_void_p),
+                                                 C.cast(self._td, C.c_void_p)))
 
     def rc_constraint_count(self):
         return int(load().rc_constraint_count(self.h))

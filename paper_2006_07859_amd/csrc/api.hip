@@ -342,7 +342,7 @@ rc_status rc_set_constraints(rc_ctx* c, uint32_t mask, const double* gamma_ref, 
   RC_TRY(sync(c));
   mg_free(c);  // the coarse levels carry constraints of the same kinds
   dense_free(c->dense);
-  RC_TRY(cons_alloc(c, c->curve, c->cons, mask, c->pts, &c->surf));
+  RC_TRY(cons_alloc(c, c->curve, c->cons, mask, c->pts, &c->surf, &c->tang));
   if (!c->pts.empty())
     RC_HIP(hipMemcpy(c->cons.ptx, c->pts_x.data(), sizeof(double) * c->pts_x.size(), hipMemcpyHostToDevice));
   if (mask == 0) return RC_OK;
@@ -365,7 +365,7 @@ static rc_status relay_constraints(rc_ctx* c) {
     RC_TRY(fetch(c, k.len0, len0.data(), c->nE));
   }
   // Phi and its negation in the projection (2 k values)
-  const size_t kmax = (size_t)c->nE + 4 + 3 * c->pts.size() + c->surf.verts.size();
+  const size_t kmax = (size_t)c->nE + 4 + 3 * c->pts.size() + c->surf.verts.size() + 2 * c->tang.edges.size();
   if (kmax > c->phi_cap) {
     hipFree(c->phi);
     RC_TRY(dalloc(&c->phi, 2 * kmax));
@@ -373,7 +373,7 @@ static rc_status relay_constraints(rc_ctx* c) {
   }
   mg_free(c);
   dense_free(c->dense);
-  RC_TRY(cons_alloc(c, c->curve, k, mask, c->pts, &c->surf));
+  RC_TRY(cons_alloc(c, c->curve, k, mask, c->pts, &c->surf, &c->tang));
   k.total0 = total0;
   RC_HIP(hipMemcpy(k.x0, x0, sizeof(double) * 3, hipMemcpyHostToDevice));
   if (!len0.empty()) RC_HIP(hipMemcpy(k.len0, len0.data(), sizeof(double) * c->nE, hipMemcpyHostToDevice));
@@ -1079,4 +1079,41 @@ extern "C" rc_status rc_mlp_fit_step(rc_mlp* m, const float* X, const float* R, 
   }
   hipFree(d);
   return st;
+}
+
+rc_status rc_set_tangent_constraints(rc_ctx* c, int32_t n, const int32_t* edges_h, const double* dirs_h) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_set_tangent_constraints"));
+  if (n < 0 || n > c->nE || (n > 0 && (!edges_h || !dirs_h))) {
+    set_error("tangent constraints: n must lie in [0, nE], with host edges and directions when positive");
+    return RC_ERR_ARG;
+  }
+  TangentSpec t;
+  t.edges.assign(edges_h, edges_h + n);
+  if (!valid_vertex_set(t.edges, c->nE, {})) {
+    set_error("tangent constraints: edge out of range or given twice");
+    return RC_ERR_ARG;
+  }
+  for (int j = 0; j < n; ++j) {
+    double X[3] = {dirs_h[3 * j], dirs_h[3 * j + 1], dirs_h[3 * j + 2]};
+    const double len = std::sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+    if (!(std::isfinite(len) && len > 0.0)) {
+      set_error("tangent constraints: a direction is zero or not finite");
+      return RC_ERR_ARG;
+    }
+    for (double& x : X) x /= len;
+    // u = X x e_m / |X x e_m| with e_m the axis of the smallest |X_m| (the first on ties), v = X x u
+    int m = 0;
+    for (int q = 1; q < 3; ++q)
+      if (std::fabs(X[q]) < std::fabs(X[m])) m = q;
+    double em[3] = {0.0, 0.0, 0.0};
+    em[m] = 1.0;
+    double u[3] = {X[1] * em[2] - X[2] * em[1], X[2] * em[0] - X[0] * em[2], X[0] * em[1] - X[1] * em[0]};
+    const double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    for (double& x : u) x /= un;
+    const double v[3] = {X[1] * u[2] - X[2] * u[1], X[2] * u[0] - X[0] * u[2], X[0] * u[1] - X[1] * u[0]};
+    t.basis.insert(t.basis.end(), {u[0], u[1], u[2], v[0], v[1], v[2]});
+  }
+  c->tang = t;
+  return relay_constraints(c);
 }

@@ -46,8 +46,8 @@ void cons_geometry(const double* gamma, const int2* edges, int nE, double* geo, 
 void cons_phi_edge(const double* geo, const double* x0, int nE, const double* len0, double* vals, double* phi_edges,
                    hipStream_t s);
 void cons_border_rows(const double* geo, const int* inc_off, const int* inc, const int2* edges, const double* x0,
-                      int nV, int bary, int total, const int* cut_edge, int ncut, double* rows, int nrows,
-                      hipStream_t s);
+                      int nV, int bary, int total, const int* tg, const double* tgb, int ntg, const int* cut_edge,
+                      int ncut, double* rows, int nrows, hipStream_t s);
 // point and surface constraints by elimination: weights (w or 1) times the free mask, x_v <- W_v x_v
 // (W_v = w_v (I - n_v n_v^T), nrm may be null), unit zero diagonals
 void free_weights(const double* w, const double* free, int nV, double* out, hipStream_t s);

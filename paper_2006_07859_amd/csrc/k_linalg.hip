@@ -579,7 +579,7 @@ void cons_phi_edge(const double* geo, const double* x0, int nE, const double* le
 }
 
 // Border rows as dense vertex vectors rows[r][nV][3], in the order barycenter (3),
-// total length (1), cut edges (1 each).
+// total length (1), tangents (2 each), cut edges (1 each).
 //   barycenter row c: at v, sum_{I at v} (l_I/2) e_c + sigma_I(v) (x_I - x0)_c T_I, sigma(i1) = -1, sigma(i2) = +1
 //   total-length row: at v, sum_{I at v} s_I(v) T_I with s(i1) = +1, s(i2) = -1
 //   cut-edge row for edge I: +T_I at i1, -T_I at i2
@@ -627,15 +627,39 @@ __global__ void k_cut_rows(const double* __restrict__ geo, const int2* __restric
   }
 }
 
+// tangent rows (Sec. 7.1, read as (u . T_I, v . T_I)): d(b . T_I) = (b - (b . T_I) T_I) / l_I at i2,
+// its negative at i1; rows row0 + 2 j (b = u) and row0 + 2 j + 1 (b = v) of tangent j
+__global__ void k_tangent_rows(const double* __restrict__ geo, const int2* __restrict__ edges,
+                               const int* __restrict__ tg, const double* __restrict__ tgb, int ntg, int row0, int nV,
+                               double* __restrict__ rows) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * ntg) return;
+  const int I = tg[i / 2];
+  const double* g = geo + 8 * (size_t)I;
+  const double* b = tgb + 6 * (i / 2) + 3 * (i % 2);
+  const double bt = b[0] * g[1] + b[1] * g[2] + b[2] * g[3];
+  const int2 e = edges[I];
+  double* r = rows + (size_t)(row0 + i) * nV * 3;
+  for (int cc = 0; cc < 3; ++cc) {
+    const double v = (b[cc] - bt * g[1 + cc]) / g[0];
+    r[3 * e.y + cc] = v;
+    r[3 * e.x + cc] = -v;
+  }
+}
+
 void cons_border_rows(const double* geo, const int* inc_off, const int* inc, const int2* edges, const double* x0,
-                      int nV, int bary, int total, const int* cut_edge, int ncut, double* rows, int nrows,
-                      hipStream_t s) {
+                      int nV, int bary, int total, const int* tg, const double* tgb, int ntg, const int* cut_edge,
+                      int ncut, double* rows, int nrows, hipStream_t s) {
   hipMemsetAsync(rows, 0, sizeof(double) * (size_t)nrows * nV * 3, s);
   hipLaunchKernelGGL(k_border_rows, dim3(cdiv(nV, 256)), dim3(256), 0, s, geo, inc_off, inc, x0, nV, bary, total,
                      rows);
+  const int row_tg = 3 * bary + total;
+  if (ntg > 0)
+    hipLaunchKernelGGL(k_tangent_rows, dim3(cdiv(2 * ntg, 64)), dim3(64), 0, s, geo, edges, tg, tgb, ntg, row_tg, nV,
+                       rows);
   if (ncut > 0)
     hipLaunchKernelGGL(k_cut_rows, dim3(cdiv(ncut, 256)), dim3(256), 0, s, geo, edges, cut_edge, ncut,
-                       3 * bary + total, nV, rows);
+                       row_tg + 2 * ntg, nV, rows);
 }
 
 // Tridiagonal coefficients of C_p W C_p^T over the path rows (chain order),

@@ -29,6 +29,15 @@ struct SurfSpec {
   bool operator!=(const SurfSpec& o) const { return !(*this == o); }
 };
 
+// Edges whose unit tangent is prescribed (Sec. 7.1), as the two rows (u . T_I, v . T_I) over an
+// orthonormal basis (u, v) of the plane orthogonal to the direction X.
+struct TangentSpec {
+  std::vector<int> edges;
+  std::vector<double> basis;  // [n][6]: u then v
+  bool operator==(const TangentSpec& o) const { return edges == o.edges && basis == o.basis; }
+  bool operator!=(const TangentSpec& o) const { return !(*this == o); }
+};
+
 struct Cons {
   uint32_t mask = 0;
   int bary = 0, total = 0, edge = 0;
@@ -38,7 +47,7 @@ struct Cons {
   // F - F C^T (C F C^T)^-1 C F, the weighted projector with W = F (and the smoother's
   // W = D^-1 F), so they add no border rows
   int npt = 0, nbt = 0, nd = 0;         // pinned vertices; barycenter + total rows; rows before the edge rows
-                                        // (nbt + 3 npt + nsf)
+                                        // (nbt + 3 npt + nsf + 2 ntg)
   double total0 = 0.0;
   std::vector<int> h_pt;                // pinned vertices, in row order
   int* pt = nullptr;
@@ -49,6 +58,12 @@ struct Cons {
   int* sf = nullptr;                    // [nsf] the held vertices, in row order
   double* sgrad = nullptr;              // [nsf][3] grad f at the prepared curve
   double* nrm = nullptr;                // [nV][3] unit normals there (zero at other vertices)
+  // tangent constraints: two rows of the projector's dense block each, after barycenter and total
+  TangentSpec tang;
+  int ntg = 0;
+  int* tg = nullptr;                    // [ntg] edges
+  double* tgb = nullptr;                // [ntg][6] bases
+  int ext_tg = 0;                       // first tangent row in the external order
   bool elim = false;                    // point or surface constraints present
   double* free = nullptr;               // [nV] 0 at pinned vertices, else 1 (elim)
   double* weff = nullptr;               // [nV] the weights of the prepared factors (w or 1) * free
@@ -208,6 +223,7 @@ struct rc_ctx {
   std::vector<int> pts;
   std::vector<double> pts_x;
   rc::SurfSpec surf;
+  rc::TangentSpec tang;
   size_t phi_cap = 0;  // rows the phi buffer holds (twice)
 };
 
@@ -222,7 +238,7 @@ rc_status fetch(rc_ctx* c, const double* dev, double* host, int n);
 bool trace_on();
 
 rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const std::vector<int>& pts = {},
-                     const SurfSpec* surf = nullptr);
+                     const SurfSpec* surf = nullptr, const TangentSpec* tang = nullptr);
 void cons_free(Cons& k);
 rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma, const double* w = nullptr);
 // With pop, the last launch also writes the operand of pop's next product,

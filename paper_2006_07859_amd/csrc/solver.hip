@@ -92,15 +92,27 @@ static bool invert_small(std::vector<double>& A, int n) {
 // ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
-// b in external order (barycenter and total length [nbt], points, edges from nd) -> path rows wp
-// and border rows wb (barycenter, total length, cut edges)
-__global__ void k_map_rhs(const double* __restrict__ b, int nbt, int nd, const int* __restrict__ path_edge, int np,
-                          const int* __restrict__ cut_edge, int ncut, double* __restrict__ wp,
-                          double* __restrict__ wb, double sign) {
+// b in external order (barycenter and total length [nbt], points, surface, tangents [2 ntg] from
+// ext_tg, edges from nd) -> path rows wp and border rows wb (barycenter, total length, tangents,
+// cut edges)
+__global__ void k_map_rhs(const double* __restrict__ b, int nbt, int ext_tg, int ntg, int nd,
+                          const int* __restrict__ path_edge, int np, const int* __restrict__ cut_edge, int ncut,
+                          double* __restrict__ wp, double* __restrict__ wb, double sign) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < np) wp[i] = sign * b[nd + path_edge[i]];
   if (i < nbt) wb[i] = sign * b[i];
-  if (i < ncut) wb[nbt + i] = sign * b[nd + cut_edge[i]];
+  if (i < 2 * ntg) wb[nbt + i] = sign * b[ext_tg + i];
+  if (i < ncut) wb[nbt + 2 * ntg + i] = sign * b[nd + cut_edge[i]];
+}
+
+// tangent rows of Phi: (u . T_I, v . T_I) from row0 (geo: the edges' T at slots 1..3)
+__global__ void k_phi_tangent(const double* __restrict__ geo, const int* __restrict__ tg,
+                              const double* __restrict__ tgb, int ntg, int row0, double* __restrict__ phi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * ntg) return;
+  const double* t = geo + 8 * (size_t)tg[i / 2] + 1;
+  const double* b = tgb + 6 * (i / 2) + 3 * (i % 2);
+  phi[row0 + i] = b[0] * t[0] + b[1] * t[1] + b[2] * t[2];
 }
 
 // The implicit surface of a surface constraint by value (kernel argument).
@@ -278,12 +290,12 @@ __global__ void k_fill_pattern(double* __restrict__ x, int n, unsigned seed) {
 // constraints of one level
 // ---------------------------------------------------------------------------
 void cons_free(Cons& k) {
-  int* ip[] = {k.path_edge, k.path_prev, k.cut_edge, k.edge_path_row, k.pt, k.sf};
+  int* ip[] = {k.path_edge, k.path_prev, k.cut_edge, k.edge_path_row, k.pt, k.sf, k.tg};
   for (int* p : ip)
     if (p) hipFree(p);
   double* dp[] = {k.x0, k.len0, k.ones, k.geo, k.geo_eval, k.vals, k.rows, k.ta, k.td, k.tc, k.Kpb, k.Z, k.Sinv,
                   k.tri_scratch, k.wp, k.yp, k.wb, k.yb, k.dots, k.rhs, k.small, k.part, k.sp_VW, k.sp_Rt, k.sp_g,
-                  k.sp_U, k.sp_tmp, k.ptx, k.free, k.weff, k.sgrad, k.nrm};
+                  k.sp_U, k.sp_tmp, k.ptx, k.free, k.weff, k.sgrad, k.nrm, k.tgb};
   for (double* p : dp)
     if (p) hipFree(p);
   if (k.prow) hipFree(k.prow);
@@ -293,7 +305,7 @@ void cons_free(Cons& k) {
 }
 
 rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const std::vector<int>& pts,
-                     const SurfSpec* surf) {
+                     const SurfSpec* surf, const TangentSpec* tang) {
   (void)c;
   cons_free(k);
   k.mask = mask;
@@ -301,6 +313,8 @@ rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const s
   k.npt = (int)pts.size();
   if (surf && surf->kind && !surf->verts.empty()) k.surf = *surf;
   k.nsf = (int)k.surf.verts.size();
+  if (tang) k.tang = *tang;
+  k.ntg = (int)k.tang.edges.size();
   k.elim = k.npt > 0 || k.nsf > 0;
   k.bary = (mask & RC_C_BARYCENTER) ? 1 : 0;
   k.total = (mask & RC_C_TOTAL_LENGTH) ? 1 : 0;
@@ -336,12 +350,14 @@ rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const s
   k.np = (int)k.h_path_edge.size();
   k.ncut = (int)k.h_cut_edge.size();
   k.nbt = 3 * k.bary + k.total;
-  k.nd = k.nbt + 3 * k.npt + k.nsf;
-  k.nb = k.nbt + k.ncut;
+  k.ext_tg = k.nbt + 3 * k.npt + k.nsf;
+  k.nd = k.ext_tg + 2 * k.ntg;
+  k.nb = k.nbt + 2 * k.ntg + k.ncut;
   k.k = k.nd + (k.edge ? nE : 0);
   if (k.nb > 120) {
-    set_error("too many loops and junction edges for edge-length constraints (at most 120 border rows: 3 + 1 "
-              "for barycenter and total length, 1 per loop and 1 per edge at a vertex of degree >= 3)");
+    set_error("too many rows in the projector's dense block (at most 120: 3 + 1 for barycenter and total length, "
+              "2 per tangent constraint, and with edge-length constraints 1 per loop and 1 per edge at a vertex of "
+              "degree >= 3)");
     return RC_ERR_UNSUPPORTED;
   }
   if (k.elim) {
@@ -356,6 +372,12 @@ rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const s
     RC_TRY(dalloc(&k.ptx, 3 * (size_t)k.npt));
     RC_HIP(hipMemcpy(k.pt, pts.data(), sizeof(int) * k.npt, hipMemcpyHostToDevice));
     RC_HIP(hipMemset(k.ptx, 0, sizeof(double) * 3 * k.npt));
+  }
+  if (k.ntg) {
+    RC_TRY(dalloc(&k.tg, k.ntg));
+    RC_TRY(dalloc(&k.tgb, 6 * (size_t)k.ntg));
+    RC_HIP(hipMemcpy(k.tg, k.tang.edges.data(), sizeof(int) * k.ntg, hipMemcpyHostToDevice));
+    RC_HIP(hipMemcpy(k.tgb, k.tang.basis.data(), sizeof(double) * 6 * k.ntg, hipMemcpyHostToDevice));
   }
   if (k.nsf) {
     RC_TRY(dalloc(&k.sf, k.nsf));
@@ -468,8 +490,8 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma,
     hipLaunchKernelGGL(k_surface_prepare, dim3(cdiv(k.nsf, 64)), dim3(64), 0, s, gamma, k.sf, k.nsf, surf_par(k),
                        k.sgrad, k.nrm);
   cons_geometry(gamma, cv.edges, nE, k.geo, s);
-  cons_border_rows(k.geo, cv.inc_off, cv.inc, cv.edges, k.x0, nV, k.bary, k.total, k.cut_edge, k.ncut, k.rows,
-                   k.nb, s);
+  cons_border_rows(k.geo, cv.inc_off, cv.inc, cv.edges, k.x0, nV, k.bary, k.total, k.tg, k.tgb, k.ntg, k.cut_edge,
+                   k.ncut, k.rows, k.nb, s);
   const int nb = k.nb, np = k.np;
   double* lo = k.tri_scratch;
   double* uinv = k.tri_scratch + np;
@@ -636,8 +658,8 @@ static void cons_min_norm(rc_ctx* c, const double* b, double* z, double* scratch
   hipStream_t s = c->stream;
   const int nV = c->nV, n3 = 3 * nV;
   const int n = std::max(k.np, std::max(k.nb, 1));
-  hipLaunchKernelGGL(k_map_rhs, dim3(cdiv(n, 256)), dim3(256), 0, s, b, k.nbt, k.nd, k.path_edge, k.np,
-                     k.cut_edge, k.ncut, k.wp, k.wb, -1.0);
+  hipLaunchKernelGGL(k_map_rhs, dim3(cdiv(n, 256)), dim3(256), 0, s, b, k.nbt, k.ext_tg, k.ntg, k.nd, k.path_edge,
+                     k.np, k.cut_edge, k.ncut, k.wp, k.wb, -1.0);
   if (k.elim) {  // (wp, wb) = -(b_C - C v)
     hipLaunchKernelGGL(k_fill, dim3(cdiv(n3, 256)), dim3(256), 0, s, z, n3, 0.0);
     hipLaunchKernelGGL(k_particular, dim3(cdiv(std::max(3 * k.npt, k.nsf), 64)), dim3(64), 0, s, b, k.nbt, k.pt,
@@ -662,7 +684,7 @@ static void cons_min_norm(rc_ctx* c, const double* b, double* z, double* scratch
   }
 }
 
-// Phi(gamma) in external order (barycenter, total length, points, surface, edges).
+// Phi(gamma) in external order (barycenter, total length, points, surface, tangents, edges).
 void cons_values(rc_ctx* c, const double* gamma, double* phi) {
   Cons& k = c->cons;
   hipStream_t s = c->stream;
@@ -679,6 +701,9 @@ void cons_values(rc_ctx* c, const double* gamma, double* phi) {
   if (k.nsf > 0)
     hipLaunchKernelGGL(k_phi_surface, dim3(cdiv(k.nsf, 64)), dim3(64), 0, s, gamma, k.sf, k.nsf, surf_par(k),
                        nbt + 3 * k.npt, phi);
+  if (k.ntg > 0)
+    hipLaunchKernelGGL(k_phi_tangent, dim3(cdiv(2 * k.ntg, 64)), dim3(64), 0, s, k.geo_eval, k.tg, k.tgb, k.ntg,
+                       k.ext_tg, phi);
 }
 
 // ---------------------------------------------------------------------------
@@ -733,7 +758,7 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
   RC_TRY(launch_assemble_dense(cv, c->alpha, c->beta, d.A, s));
   if (kk > 0) {
     // dense C in external order: the border rows of barycenter and total length, the point
-    // rows, the surface rows, then the edge rows
+    // rows, the surface rows, the tangent rows of the border, then the edge rows
     RC_HIP(hipMemsetAsync(d.Cd, 0, sizeof(double) * (size_t)kk * n, s));
     if (k.nbt > 0)
       RC_HIP(hipMemcpyAsync(d.Cd, k.rows, sizeof(double) * (size_t)k.nbt * n, hipMemcpyDeviceToDevice, s));
@@ -741,6 +766,9 @@ static rc_status dense_prepare(rc_ctx* c, const Curve& cv, Cons& k, Dense& d, co
     if (k.nsf)
       hipLaunchKernelGGL(k_dense_C_surface, dim3(cdiv(k.nsf, 64)), dim3(64), 0, s, k.sgrad, k.sf, k.nsf,
                          k.nbt + 3 * k.npt, nV, d.Cd);
+    if (k.ntg)  // the tangent rows of the border, after the surface rows
+      RC_HIP(hipMemcpyAsync(d.Cd + (size_t)k.ext_tg * n, k.rows + (size_t)k.nbt * n,
+                            sizeof(double) * (size_t)2 * k.ntg * n, hipMemcpyDeviceToDevice, s));
     if (k.edge) dense_C_edges(k.geo, cv.edges, cv.nE, k.nd, nV, k.free, d.Cd, s);
     dense_gemm(d.Cd, d.Cd, d.CtC, n, n, kk, 0.0, true, s);
   } else {
@@ -1029,8 +1057,8 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
     const int n = cv.nV;
     if (c->mg_weighted) {  // factors of C W C^T, W = D^-1
       Cons& Kw = level_cons_w(c, l);
-      if (Kw.mask != K.mask || Kw.h_pt != K.h_pt || Kw.surf != K.surf || !Kw.geo)
-        RC_TRY(cons_alloc(c, cv, Kw, K.mask, K.h_pt, &K.surf));
+      if (Kw.mask != K.mask || Kw.h_pt != K.h_pt || Kw.surf != K.surf || Kw.tang != K.tang || !Kw.geo)
+        RC_TRY(cons_alloc(c, cv, Kw, K.mask, K.h_pt, &K.surf, &K.tang));
       RC_HIP(hipMemcpyAsync(Kw.x0, K.x0, sizeof(double) * 3, hipMemcpyDeviceToDevice, s));
       hipLaunchKernelGGL(k_recip, dim3(cdiv(n, 256)), dim3(256), 0, s, st.diag, n, st.w);
       RC_TRY(cons_prepare(c, cv, Kw, l == 0 ? gamma : c->levels[l]->gamma, st.w));
@@ -1708,6 +1736,7 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
         double tol = ls.proj_tol * lbar;
         if (K.bary && i < 3) tol *= Ltot;             // barycenter rows carry units of length^2
         else if (K.total && i == 3 * K.bary) tol *= Ltot / lbar;  // total length: relative to L
+        else if (i >= K.ext_tg && i < K.ext_tg + 2 * K.ntg) tol = ls.proj_tol;  // tangent rows: dimensionless
         if (!std::isfinite(phi_h[i]) || std::fabs(phi_h[i]) > tol) done = false;
       }
       if (done) {
