@@ -939,8 +939,8 @@ __global__ __launch_bounds__(kSpThreads) void k_proj_rows(const ProjData d, cons
     }
   }
   // border dot products over the vertices, spread over the workgroups
-  for (int i = blk * kSpThreads + t; i < nV; i += gridDim.x * kSpThreads) {
-    if (d.nrm) {  // rows . (W x)
+  if (d.nrm) {  // rows . (W x) with the normal parts
+    for (int i = blk * kSpThreads + t; i < nV; i += gridDim.x * kSpThreads) {
       double x0 = x[3 * i], x1 = x[3 * i + 1], x2 = x[3 * i + 2];
       proj_w_apply(d, i, x0, x1, x2);
 #pragma unroll
@@ -949,15 +949,17 @@ __global__ __launch_bounds__(kSpThreads) void k_proj_rows(const ProjData d, cons
           const double* rv = d.rows + ((size_t)r * nV + i) * 3;
           acc[r] += rv[0] * x0 + rv[1] * x1 + rv[2] * x2;
         }
-      continue;
     }
-    const double wi = d.w ? d.w[i] : 1.0;
+  } else {
+    for (int i = blk * kSpThreads + t; i < nV; i += gridDim.x * kSpThreads) {
+      const double wi = d.w ? d.w[i] : 1.0;
 #pragma unroll
-    for (int r = 0; r < kProjMaxBorder; ++r)
-      if (r < nb) {
-        const double* rv = d.rows + ((size_t)r * nV + i) * 3;
-        acc[r] += wi * (rv[0] * x[3 * i] + rv[1] * x[3 * i + 1] + rv[2] * x[3 * i + 2]);
-      }
+      for (int r = 0; r < kProjMaxBorder; ++r)
+        if (r < nb) {
+          const double* rv = d.rows + ((size_t)r * nV + i) * 3;
+          acc[r] += wi * (rv[0] * x[3 * i] + rv[1] * x[3 * i + 1] + rv[2] * x[3 * i + 2]);
+        }
+    }
   }
   if (np > 0) {
     tri_local_solve(d.lo, d.uinv, d.tc, L, blk, v, wa, wb);
