@@ -17,4 +17,6 @@ from .curves import (  # noqa: F401
     theta_graph,
     tennis_ball,
     torus_knot,
+    icosphere,
+    torus_mesh,
 )

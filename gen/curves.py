@@ -25,6 +25,8 @@ __all__ = [
     "theta_graph",
     "tennis_ball",
     "torus_knot",
+    "icosphere",
+    "torus_mesh",
 ]
 
 
@@ -210,3 +212,43 @@ def torus_knot(n: int = 256, p: int = 2, q: int = 3, R: float = 1.0, r: float = 
     if jitter_var > 0:
         g = g + np.random.default_rng(seed).normal(0.0, np.sqrt(jitter_var), size=g.shape)
     return g, loop_edges(n)
+
+
+def icosphere(level: int = 2, radius: float = 1.0, center=(0.0, 0.0, 0.0)):
+    """Triangulated sphere: the octahedron's 8 faces split ``level`` times into 4
+    (edge midpoints pushed out to the sphere).  Returns ``(P, F)``: vertices
+    float64 [nP, 3] and triangles int32 [8 * 4^level, 3], outward oriented."""
+    P = [np.array(v, dtype=np.float64) for v in
+         ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1))]
+    F = [(0, 2, 4), (2, 1, 4), (1, 3, 4), (3, 0, 4), (2, 0, 5), (1, 2, 5), (3, 1, 5), (0, 3, 5)]
+    for _ in range(level):
+        mid = {}
+
+        def m(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                v = P[a] + P[b]
+                P.append(v / np.linalg.norm(v))
+                mid[key] = len(P) - 1
+            return mid[key]
+
+        F = [t for a, b, c in F for t in ((a, m(a, b), m(c, a)), (b, m(b, c), m(a, b)), (c, m(c, a), m(b, c)),
+                                           (m(a, b), m(b, c), m(c, a)))]
+    return radius * np.array(P) + np.asarray(center, dtype=np.float64), np.array(F, dtype=np.int32)
+
+
+def torus_mesh(nu: int = 32, nv: int = 16, R: float = 1.0, r: float = 0.3, center=(0.0, 0.0, 0.0)):
+    """Triangulated torus about the z axis: an ``nu`` x ``nv`` grid in the angles
+    (u around the axis, v around the tube), two triangles per cell.  Returns ``(P, F)``."""
+    u = 2.0 * np.pi * np.arange(nu) / nu
+    v = 2.0 * np.pi * np.arange(nv) / nv
+    U, V = np.meshgrid(u, v, indexing="ij")
+    P = np.stack([(R + r * np.cos(V)) * np.cos(U), (R + r * np.cos(V)) * np.sin(U), r * np.sin(V)], axis=-1)
+    P = P.reshape(-1, 3) + np.asarray(center, dtype=np.float64)
+    idx = lambda i, j: (i % nu) * nv + (j % nv)
+    F = []
+    for i in range(nu):
+        for j in range(nv):
+            F.append((idx(i, j), idx(i + 1, j), idx(i + 1, j + 1)))
+            F.append((idx(i, j), idx(i + 1, j + 1), idx(i, j + 1)))
+    return P, np.array(F, dtype=np.int32)

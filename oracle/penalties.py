@@ -10,7 +10,12 @@ penalties), each with its differential with respect to the vertex positions:
   I and J the two edges at v;
 * field potential: sum over edges of l_I |T_I x X|^2 for a fixed unit vector
   X (a constant field; the paper's field is sampled at the edge midpoint,
-  and a constant field does not depend on it).
+  and a constant field does not depend on it);
+* surface potential of a triangulated surface M (vertices P, triangles F):
+  the double integral of |x_M - gamma|^-p, p = beta - alpha, over the curve
+  and M, with one sample per edge (its midpoint x_I, weight l_I) and one per
+  triangle (its centroid c_T, weight its area A_T):
+  sum_I l_I phi(x_I), phi(x) = sum_T A_T |c_T - x|^-p.
 
 The differentials follow from dl_I = T_I . (d gamma_i2 - d gamma_i1) and
 dT_I = (I - T_I T_I^T)(d gamma_i2 - d gamma_i1) / l_I.
@@ -22,7 +27,8 @@ import numpy as np
 
 from .tpe import edge_geometry
 
-__all__ = ["total_length", "length_difference", "field_potential", "penalties"]
+__all__ = ["total_length", "length_difference", "field_potential", "penalties", "triangle_samples",
+           "surface_field", "surface_potential"]
 
 
 def _scatter(edges, nV, gI):
@@ -84,4 +90,41 @@ def penalties(gamma, edges, w_length=0.0, w_diff=0.0, w_field=0.0, X=(0.0, 0.0, 
             e_, d_ = f()
             E += w * e_
             d += w * d_
+    return E, d
+
+
+def triangle_samples(P, F):
+    """Centroids c_T [nF][3] and areas A_T [nF] of the triangles F of the vertices P."""
+    P = np.asarray(P, dtype=np.float64)
+    F = np.asarray(F)
+    a, b, c = P[F[:, 0]], P[F[:, 1]], P[F[:, 2]]
+    return (a + b + c) / 3.0, 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+
+
+def surface_field(x, P, F, p):
+    """phi(x) = sum_T A_T |c_T - x|^-p at the points x [m][3], and its gradient
+    p sum_T A_T |c_T - x|^(-p-2) (c_T - x)."""
+    cT, AT = triangle_samples(P, F)
+    x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+    phi = np.zeros(len(x))
+    grad = np.zeros((len(x), 3))
+    for k in range(len(x)):
+        d = cT - x[k]
+        r2 = (d * d).sum(1)
+        phi[k] = (AT * r2 ** (-0.5 * p)).sum()
+        grad[k] = p * ((AT * r2 ** (-0.5 * p - 1.0))[:, None] * d).sum(0)
+    return phi, grad
+
+
+def surface_potential(gamma, edges, P, F, p):
+    """E = sum_I l_I phi(x_I) and its vertex differential: at the edge's ends
+    -+T_I phi(x_I) + (l_I / 2) grad phi(x_I) (x_I moves by half of each end)."""
+    g, e = np.asarray(gamma, dtype=np.float64), np.asarray(edges)
+    ell, T, x = edge_geometry(g, e)
+    phi, grad = surface_field(x, P, F, p)
+    E = float((ell * phi).sum())
+    d = np.zeros_like(g)
+    half = 0.5 * ell[:, None] * grad
+    np.add.at(d, e[:, 1], T * phi[:, None] + half)
+    np.add.at(d, e[:, 0], -T * phi[:, None] + half)
     return E, d

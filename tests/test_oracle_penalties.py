@@ -10,12 +10,17 @@
   difference by lambda^2; all three are invariant under translations and the
   field potential under rotations that fix X.
 * Differentials against central differences of the energies.
+* Triangulated-surface potential: the generated meshes' areas; on refined
+  spheres the centroid-quadrature field converges at second order to the
+  closed-form shell potential of the sphere obstacle; its differential against
+  central differences; scaling lambda^(3 - p) and rigid-motion invariance.
 """
 
 import numpy as np
 import pytest
 
 import gen
+from oracle import obstacle
 from oracle import penalties as pen
 
 
@@ -78,3 +83,50 @@ def test_differentials_match_central_differences():
                 gm[v, c] -= h
                 fd = (f(gp)[0] - f(gm)[0]) / (2 * h)
                 assert d[v, c] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+# --- triangulated-surface potential (Sec. 7.1) -------------------------------
+
+
+def test_triangle_samples_and_meshes():
+    P, F = gen.icosphere(3, radius=0.5)
+    cT, AT = pen.triangle_samples(P, F)
+    assert len(F) == 8 * 4 ** 3 and np.allclose(np.linalg.norm(P, axis=1), 0.5)
+    # inscribed polyhedron: its area approaches 4 pi R^2 from below
+    assert 0.97 * np.pi < AT.sum() < np.pi
+    P, F = gen.torus_mesh(64, 32, R=1.0, r=0.3)
+    _, AT = pen.triangle_samples(P, F)
+    assert AT.sum() == pytest.approx(4 * np.pi ** 2 * 1.0 * 0.3, rel=5e-3)
+
+
+@pytest.mark.parametrize("p", [2.0, 2.5])
+def test_surface_field_converges_to_the_sphere_closed_form(p):
+    """On a refined triangulated sphere the centroid-quadrature field approaches the shell
+    potential's closed form (the sphere obstacle's) at second order in the mesh size."""
+    x = np.array([[1.7, 0.2, -0.3], [0.0, 0.0, 2.5]])
+    exact = obstacle.shell_potential(np.linalg.norm(x, axis=1), 1.0, p)
+    errs = []
+    for lev in (3, 4, 5):
+        P, F = gen.icosphere(lev)
+        phi, _ = pen.surface_field(x, P, F, p)
+        errs.append(np.abs(phi / exact - 1).max())
+    # second order in the mesh size (each level halves it): the error falls about 4x per level
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5 and errs[2] < 1.5e-3
+
+
+def test_surface_potential_differential_and_scaling():
+    g, e = gen.trefoil(24, seed=1)
+    g = 0.3 * g + [0.0, 0.0, 2.2]
+    P, F = gen.torus_mesh(12, 8, R=1.0, r=0.3)
+    E, d = pen.surface_potential(g, e, P, F, 2.5)
+    h = 1e-6
+    for v, c in [(0, 0), (5, 2), (17, 1)]:
+        gp, gm = g.copy(), g.copy()
+        gp[v, c] += h
+        gm[v, c] -= h
+        fd = (pen.surface_potential(gp, e, P, F, 2.5)[0] - pen.surface_potential(gm, e, P, F, 2.5)[0]) / (2 * h)
+        assert d[v, c] == pytest.approx(fd, rel=1e-6, abs=1e-9 * np.abs(d).max())
+    # E(lambda gamma, lambda M) = lambda^(1 + 2 - p) E; a rigid motion of both leaves it unchanged
+    assert pen.surface_potential(1.7 * g, e, 1.7 * P, F, 2.5)[0] == pytest.approx(1.7 ** 0.5 * E, rel=1e-12)
+    q, _ = np.linalg.qr(np.random.default_rng(2).normal(size=(3, 3)))
+    assert pen.surface_potential(g @ q.T + 1.0, e, P @ q.T + 1.0, F, 2.5)[0] == pytest.approx(E, rel=1e-12)
