@@ -501,6 +501,26 @@ rc_status rc_set_obstacle(rc_ctx* ctx, const double* center_h, double radius, do
  * (else RC_ERR_ARG); all zero removes them.  Not for batch contexts. */
 rc_status rc_set_penalties(rc_ctx* ctx, double w_length, double w_diff, double w_field, const double* field_h);
 
+/* Triangulated-surface potential (Sec. 7.1, surface potential): weight times
+ * the double integral of |x_M - gamma|^-(beta - alpha) over the curve and the
+ * surface M, sampled at the edge midpoints x_I (weight l_I) and the triangle
+ * centroids c_T (weight the area A_T): weight sum_I l_I sum_T A_T
+ * |c_T - x_I|^-(beta - alpha), added with its differential to every all-pairs
+ * energy and differential of the context (like rc_set_penalties).  The sum
+ * over triangles runs over a bounding-sphere tree of M built here on the host
+ * (the surface does not move): a node whose triangles lie in a sphere of
+ * radius r around their area-weighted centre c_B, with r < theta |c_B - x_I|,
+ * counts as one sample of its total area at c_B; theta = 0 sums every
+ * triangle.  P_h: HOST double [nP][3]; F_h: HOST int32 [nF][3] vertex indices
+ * (orientation unused).  weight finite and >= 0, 0 removes the potential;
+ * theta in [0, 1).  Errors: RC_ERR_ARG (weight or theta out of range, fewer
+ * than 3 vertices or 1 triangle, an index out of range, a non-finite vertex).
+ * Not for batch contexts; rc_step with a Barnes-Hut energy (bh_theta > 0)
+ * rejects it as it rejects the penalties.  A midpoint on a centroid gives an
+ * infinite energy. */
+rc_status rc_set_surface_potential(rc_ctx* ctx, int32_t nP, const double* P_h, int32_t nF, const int32_t* F_h,
+                                   double weight, double theta);
+
 /* ------------------------------------------------------------------------
  * Batches: many independent curve networks ("instances", e.g. packings of
  * closed loops) in one context.  Pair sums (energy, differential, operator)

@@ -36,7 +36,7 @@ EXPORTED = [
     "rc_sobolev_gradient",
     "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_bh_last_work", "rc_midpoint_differential",
     "rc_profile_enable", "rc_profile_read", "rc_lowp_assemble", "rc_lowp_apply", "rc_set_obstacle",
-    "rc_set_penalties",
+    "rc_set_penalties", "rc_set_surface_potential",
     "rc_create_batch", "rc_batch_size", "rc_batch_energies", "rc_batch_tiling", "rc_default_batch_opts",
     "rc_batch_set_constraints", "rc_batch_gradient", "rc_batch_step", "rc_batch_pcg_state", "rc_batch_autotune",
     "rc_batch_sobolev_apply", "rc_mlp_n_params", "rc_mlp_create", "rc_mlp_destroy", "rc_mlp_get", "rc_mlp_set", "rc_mlp_forward",
@@ -118,6 +118,7 @@ def load():
         "rc_set_point_constraints": (I32, [P, I32, P, P]),
         "rc_set_surface_constraints": (I32, [P, I32, P, I32, P]),
         "rc_set_tangent_constraints": (I32, [P, I32, P, P]),
+        "rc_set_surface_potential": (I32, [P, I32, P, I32, P, D, D]),
         "rc_constraint_values": (I32, [P, P, P]),
         "rc_constraint_count": (I32, [P]),
         "rc_project": (I32, [P, P, P, P]),
@@ -424,6 +425,15 @@ class Context:
         self._f = (C.c_double * 3)(*[float(v) for v in field])
         _check(load().rc_set_penalties(self.h, float(w_length), float(w_diff), float(w_field),
                                        C.cast(self._f, C.c_void_p)))
+
+    def rc_set_surface_potential(self, P, F, weight=1.0, theta=0.0):
+        """Triangulated-surface potential of the mesh (P [nP][3], F [nF][3]) with a weight and
+        tree opening parameter theta (0 = every triangle)."""
+        P = np.ascontiguousarray(P, dtype=np.float64).reshape(-1, 3)
+        F = np.ascontiguousarray(F, dtype=np.int32).reshape(-1, 3)
+        self._spP, self._spF = P, F
+        _check(load().rc_set_surface_potential(self.h, len(P), P.ctypes.data_as(C.c_void_p), len(F),
+                                               F.ctypes.data_as(C.c_void_p), float(weight), float(theta)))
 
     def rc_bh_last_work(self):
         f, n, nodes, depth = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32()

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "librcurves.so")
 SOURCES = ["curve.hip", "k_pairs.hip", "k_linalg.hip", "solver.hip", "api.hip", "k_bvh.hip", "k_lowp.hip",
-           "batch.hip", "k_learn.hip", "noalloc.hip", "k_vpairs.hip", "k_ccd.hip", "k_bct.hip"]
+           "batch.hip", "k_learn.hip", "noalloc.hip", "k_vpairs.hip", "k_ccd.hip", "k_bct.hip", "k_surfpot.hip"]
 ARCH = os.environ.get("RC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -572,7 +572,7 @@ rc_status rc_step(rc_ctx* c, double* gamma, const rc_solve_opts* so, const rc_ls
     set_error("rc_step: bh_theta must be 0 or lie in (0, 0.5)");
     return RC_ERR_ARG;
   }
-  if (l.bh_theta > 0.0 && (c->curve.pen.on || c->curve.obstacle.on)) {
+  if (l.bh_theta > 0.0 && (c->curve.pen.on || c->curve.obstacle.on || c->curve.spot.on)) {
     set_error("rc_step: the Barnes-Hut evaluation (bh_theta > 0) carries no penalties or obstacle");
     return RC_ERR_UNSUPPORTED;
   }
@@ -793,6 +793,43 @@ extern "C" rc_status rc_set_penalties(rc_ctx* c, double w_length, double w_diff,
   p.w_field = w_field;
   for (int k = 0; k < 3; ++k) p.X[k] = X[k];
   p.on = w_length > 0.0 || w_diff > 0.0 || w_field > 0.0;
+  return RC_OK;
+}
+
+extern "C" rc_status rc_set_surface_potential(rc_ctx* c, int32_t nP, const double* P_h, int32_t nF, const int32_t* F_h,
+                                              double weight, double theta) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_set_surface_potential"));
+  if (!std::isfinite(weight) || weight < 0.0 || !(theta >= 0.0 && theta < 1.0)) {
+    set_error("rc_set_surface_potential: weight must be finite and >= 0, theta in [0, 1)");
+    return RC_ERR_ARG;
+  }
+  SurfacePotential& sp = c->curve.spot;
+  if (weight == 0.0) {
+    RC_TRY(sync(c));
+    sp.release();
+    return RC_OK;
+  }
+  if (nP < 3 || nF < 1 || !P_h || !F_h) {
+    set_error("rc_set_surface_potential: need at least 3 vertices, 1 triangle and host arrays");
+    return RC_ERR_ARG;
+  }
+  for (int64_t i = 0; i < 3 * (int64_t)nF; ++i)
+    if (F_h[i] < 0 || F_h[i] >= nP) {
+      set_error("rc_set_surface_potential: triangle vertex out of range");
+      return RC_ERR_ARG;
+    }
+  for (int64_t i = 0; i < 3 * (int64_t)nP; ++i)
+    if (!std::isfinite(P_h[i])) {
+      set_error("rc_set_surface_potential: non-finite surface vertex");
+      return RC_ERR_ARG;
+    }
+  RC_TRY(sync(c));
+  RC_TRY(build_surface_potential(sp, P_h, nP, F_h, nF));
+  sp.w = weight;
+  sp.p = c->beta - c->alpha;
+  sp.theta = theta;
+  sp.on = true;
   return RC_OK;
 }
 

@@ -290,6 +290,7 @@ void Curve::release() {
                   vinfo, vg[0], vg[1], vg[2], vpart, vout};
   for (void* p : ptrs)
     if (p) hipFree(p);
+  spot.release();
   vp = false;
   vinfo = nullptr;
   vg[0] = vg[1] = vg[2] = nullptr;

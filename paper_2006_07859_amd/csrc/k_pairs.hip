@@ -905,6 +905,7 @@ __global__ void k_penalties(const V4<double>* __restrict__ GA, const V4<double>*
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 rc_status launch_penalties(const Curve& c, bool grad, hipStream_t s) {
+  if (c.spot.on) RC_TRY(launch_surface_potential(c, grad, s));
   if (!c.pen.on) return RC_OK;
   const Penalties& p = c.pen;
   hipLaunchKernelGGL(k_penalties, dim3(cdiv(c.nE, 256)), dim3(256), 0, s, (const V4<double>*)c.gd.a,

@@ -142,6 +142,22 @@ struct Penalties {
   double X[3] = {0, 0, 1};
 };
 
+// Triangulated-surface potential of Sec. 7.1: weight w times sum_I l_I phi(x_I),
+// phi(x) = sum_T A_T |c_T - x|^-p (p = beta - alpha; edge midpoints x_I,
+// triangle centroids c_T and areas A_T), summed over a bounding-sphere tree of
+// the triangles built once on the host (the surface does not move): a node
+// whose sphere of radius r around its area-weighted centre c_B satisfies
+// r < theta |c_B - x| contributes A_B |c_B - x|^-p; theta = 0 sums every
+// triangle.
+struct SurfacePotential {
+  bool on = false;
+  double w = 0, p = 0, theta = 0;
+  int n_nodes = 0, nF = 0, depth = 0;
+  void* nodes = nullptr;   // [n_nodes] tree nodes (k_surfpot.hip)
+  double* tris = nullptr;  // [nF][4] centroid, area, in leaf order
+  void release();
+};
+
 // A curve network on the device (the finest level, or a multigrid level).
 struct Curve {
   int nV = 0, nE = 0;
@@ -201,6 +217,7 @@ struct Curve {
   const int* inst_mask = nullptr;  // when set, work items of instances with mask 0 are skipped
   Obstacle obstacle;               // applied by launch_tpe when on
   Penalties pen;                   // applied by launch_tpe when on
+  SurfacePotential spot;           // applied by launch_tpe when on
 
   rc_status init(int nV_, int nE_, const int* edges_h);
   rc_status set_instances(int n_inst_, const int* voff_h);
@@ -248,6 +265,10 @@ void launch_vertex_geometry(const Curve& c, const double* gamma, hipStream_t s);
 rc_status launch_tpe_vp_pairs(const Curve& c, double beta, bool grad, hipStream_t s);
 // Adds the penalties (c.pen) to the per-edge energy / endpoint-derivative slots of edge_out.
 rc_status launch_penalties(const Curve& c, bool grad, hipStream_t s);
+// k_surfpot.hip: the tree of a triangulated surface (host P [nP][3], F [nF][3]) and the potential's
+// per-edge energy and endpoint derivatives added to c.edge_out
+rc_status build_surface_potential(SurfacePotential& sp, const double* P_h, int nP, const int* F_h, int nF);
+rc_status launch_surface_potential(const Curve& c, bool grad, hipStream_t s);
 rc_status launch_tpe_vp_finish(const Curve& c, double beta, bool grad, double* dE, hipStream_t s);
 // Shared tail of the edge-midpoint kernels: sums nparts chunks of the
 // 10-slot partials, writes energy and dE.
