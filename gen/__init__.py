@@ -19,4 +19,5 @@ from .curves import (  # noqa: F401
     torus_knot,
     icosphere,
     torus_mesh,
+    star_graph,
 )

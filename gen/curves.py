@@ -27,6 +27,7 @@ __all__ = [
     "torus_knot",
     "icosphere",
     "torus_mesh",
+    "star_graph",
 ]
 
 
@@ -162,25 +163,26 @@ def packing_batch(n_instances: int = 512, seed: int = 0, **kw):
     return [packing_instance(rng, **kw) for _ in range(n_instances)]
 
 
-def theta_graph(n_arc: int = 32, n_arcs: int = 3, seed: int = 0, jitter_var: float = 1e-4):
-    """A curve network with two junctions (Sec. 7.3): ``n_arcs`` arcs of ``n_arc``
-    edges each join vertex 0 at (-1, 0, 0) to vertex 1 at (1, 0, 0).
+def theta_graph(n_arc: int = 32, n_arcs: int = 3, seed: int = 0, jitter: float = 0.1):
+    """A curve network with two junctions (Sec. 7.3): ``n_arcs`` arcs of ``n_arc`` edges each join
+    vertex 0 at (-1, 0, 0) to vertex 1 at (1, 0, 0).
 
     Arc k runs through ``(-cos(pi t), r sin(pi t) cos(phi_k), r sin(pi t) sin(phi_k))``,
     ``t`` in [0, 1], with ``phi_k = 2 pi k / n_arcs`` and ``r = 0.8``, its interior
-    vertices numbered consecutively after the two junctions; i.i.d. Gaussian jitter
-    of variance ``jitter_var`` moves the interior vertices.  Edges are oriented
-    along t.
+    vertices numbered consecutively after the two junctions; i.i.d. Gaussian jitter of
+    standard deviation ``jitter`` times the arc's mean edge length moves the interior
+    vertices.  Edges are oriented along t.
     """
     rng = np.random.default_rng(seed)
     pts = [np.array([-1.0, 0.0, 0.0]), np.array([1.0, 0.0, 0.0])]
     edges = []
     for k in range(n_arcs):
         phi = 2.0 * np.pi * k / n_arcs
-        t = np.arange(1, n_arc) / n_arc
+        t = np.arange(0, n_arc + 1) / n_arc
         arc = np.stack([-np.cos(np.pi * t), 0.8 * np.sin(np.pi * t) * np.cos(phi),
                         0.8 * np.sin(np.pi * t) * np.sin(phi)], axis=1)
-        arc = arc + rng.normal(0.0, np.sqrt(jitter_var), size=arc.shape)
+        h = np.linalg.norm(np.diff(arc, axis=0), axis=1).mean()
+        arc = arc[1:-1] + rng.normal(0.0, jitter * h, size=(n_arc - 1, 3))
         first = len(pts)
         pts.extend(arc)
         ids = [0] + list(range(first, first + n_arc - 1)) + [1]
@@ -252,3 +254,24 @@ def torus_mesh(nu: int = 32, nv: int = 16, R: float = 1.0, r: float = 0.3, cente
             F.append((idx(i, j), idx(i + 1, j), idx(i + 1, j + 1)))
             F.append((idx(i, j), idx(i + 1, j + 1), idx(i, j + 1)))
     return P, np.array(F, dtype=np.int32)
+
+
+def star_graph(n_arm: int = 64, n_arms: int = 3, seed: int = 0, jitter: float = 0.1):
+    """A network with one junction: ``n_arms`` open arms of ``n_arm`` edges from vertex 0 at
+    the origin; arm k runs along ``(t cos phi_k, t sin phi_k, 0.3 sin(pi t))``, t in (0, 1]
+    (phi_k = 2 pi k / n_arms), plus i.i.d. Gaussian jitter of standard deviation ``jitter``
+    times the arm's mean edge length on the arm vertices.  Edges are oriented outwards."""
+    rng = np.random.default_rng(seed)
+    pts = [np.zeros(3)]
+    edges = []
+    for k in range(n_arms):
+        phi = 2.0 * np.pi * k / n_arms
+        t = np.arange(0, n_arm + 1) / n_arm
+        arm = np.stack([t * np.cos(phi), t * np.sin(phi), 0.3 * np.sin(np.pi * t)], axis=1)
+        h = np.linalg.norm(np.diff(arm, axis=0), axis=1).mean()
+        arm = arm[1:] + rng.normal(0.0, jitter * h, size=(n_arm, 3))
+        first = len(pts)
+        pts.extend(arm)
+        ids = [0] + list(range(first, first + n_arm))
+        edges.extend([ids[q], ids[q + 1]] for q in range(n_arm))
+    return np.array(pts), np.array(edges, dtype=np.int32)

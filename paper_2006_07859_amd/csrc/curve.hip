@@ -75,6 +75,44 @@ std::vector<Chain> chains_of(const Curve& c, const std::vector<char>* keep) {
   return out;
 }
 
+// Arcs of any graph: the maximal paths whose interior vertices have degree 2,
+// from a vertex of another degree (a junction or an end) to the next one (the
+// same vertex for an arc that closes on itself), then the components without
+// such vertices as closed loops.  For degree <= 2 graphs, chains_of.
+std::vector<Chain> arcs_of(const Curve& c) {
+  if (c.chain) return chains_of(c);
+  std::vector<Chain> out;
+  std::vector<char> used(c.nE, 0);
+  auto deg = [&](int v) { return c.h_inc_off[v + 1] - c.h_inc_off[v]; };
+  auto other = [&](int I, int v) { return c.h_edges[2 * I] == v ? c.h_edges[2 * I + 1] : c.h_edges[2 * I]; };
+  for (int v0 = 0; v0 < c.nV; ++v0) {
+    if (deg(v0) == 2 || deg(v0) == 0) continue;
+    for (int k0 = c.h_inc_off[v0]; k0 < c.h_inc_off[v0 + 1]; ++k0) {
+      int I = c.h_inc[k0] >> 1;
+      if (used[I]) continue;
+      Chain ch;
+      ch.verts.push_back(v0);
+      int v = v0;
+      while (true) {
+        used[I] = 1;
+        ch.edges.push_back(I);
+        const int w = other(I, v);
+        ch.verts.push_back(w);
+        if (deg(w) != 2) break;
+        int next = -1;
+        for (int k = c.h_inc_off[w]; k < c.h_inc_off[w + 1]; ++k)
+          if ((c.h_inc[k] >> 1) != I) next = c.h_inc[k] >> 1;
+        v = w;
+        I = next;
+      }
+      out.push_back(std::move(ch));
+    }
+  }
+  std::vector<char> keep(c.nE);
+  for (int I = 0; I < c.nE; ++I) keep[I] = used[I] ? 0 : 1;
+  for (Chain& ch : chains_of(c, &keep)) out.push_back(std::move(ch));
+  return out;
+}
 
 rc_status Curve::init(int nV_, int nE_, const int* edges_h) {
   nV = nV_;

@@ -76,6 +76,8 @@ struct Curve;
 // Chains of a degree <= 2 graph; with keep, of the subgraph of the kept edges
 // (whose vertices must have at most two kept edges).
 std::vector<Chain> chains_of(const Curve& c, const std::vector<char>* keep = nullptr);
+// Arcs between vertices of degree != 2 (and closed loops) of any graph.
+std::vector<Chain> arcs_of(const Curve& c);
 
 // Pairs of edges at most kBand apart along a chain are evaluated in FP64 by
 // the near-band kernel when the pair kernels run in FP32 (see k_pairs.hip).

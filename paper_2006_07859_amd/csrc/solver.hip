@@ -873,31 +873,32 @@ void mg_free(rc_ctx* c) {
 
 static rc_status mg_build(rc_ctx* c) {
   if (c->mg_built) return RC_OK;
-  if (!c->curve.chain) {
-    set_error("multigrid needs every vertex to have degree <= 2");
-    return RC_ERR_UNSUPPORTED;
-  }
   mg_free(c);
   c->levels.emplace_back(nullptr);
   const Curve* fine = &c->curve;
   std::vector<int> fine_pts = c->cons.h_pt;
   SurfSpec fine_surf = c->cons.surf;
   while (fine->nV > c->mg_min) {
-    std::vector<Chain> chs = chains_of(*fine);
-    // black/white coarsening: keep even chain positions, and both ends of open paths
+    // loops and open paths; with junctions, the arcs between vertices of degree != 2
+    std::vector<Chain> chs = arcs_of(*fine);
+    // black/white coarsening: keep even chain positions, and both ends of open paths and arcs
+    // (a junction is kept once, whatever the number of its arcs); an arc of at most 3 edges keeps
+    // all its vertices (coarsened, two arcs between the same junctions could become one edge)
     std::vector<int> coarse_id(fine->nV, -1), fine_of, cedges;
     std::vector<int2> prolong(fine->nV, make_int2(-1, -1));
     bool ok = true;
     for (const Chain& ch : chs) {
       const int m = (int)ch.verts.size();
-      if (ch.loop && m < 12) {
+      const bool closed_arc = !ch.loop && ch.verts.front() == ch.verts.back();
+      if ((ch.loop && m < 12) || (closed_arc && m < 13)) {
         ok = false;
         break;
       }
       std::vector<int> keep;
       for (int i = 0; i < m; ++i)
-        if (i % 2 == 0 || (!ch.loop && i == m - 1)) keep.push_back(i);
+        if (i % 2 == 0 || (!ch.loop && (i == m - 1 || m < 5))) keep.push_back(i);
       for (int i : keep) {
+        if (coarse_id[ch.verts[i]] >= 0) continue;
         coarse_id[ch.verts[i]] = (int)fine_of.size();
         fine_of.push_back(ch.verts[i]);
       }
