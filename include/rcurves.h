@@ -178,6 +178,11 @@ typedef struct {
                             the edge-midpoint discretisation, leaf size 32) with this parameter, for
                             large curves; the energy0 given to rc_line_search_step must then be one
                             too.  0 = the exact all-pairs sums */
+  int32_t bh_refit;      /* with bh_theta > 0: 1 = the trial energies re-fit the tree that rc_step
+                            built at the step's curve (rc_bh_refit_differential) instead of building a
+                            new one; 0 (default) = build at every trial.  The two approximations of a
+                            trial energy differ by about as much as the Armijo margin of a step on a
+                            large curve, so they can accept different lengths */
 } rc_ls_opts;
 
 typedef struct {
@@ -446,6 +451,17 @@ rc_status rc_sobolev_apply_bct(rc_ctx* ctx, const double* gamma, const double* X
  * energy: device double [1]; dE: device double [nV][3]. */
 rc_status rc_bh_differential(rc_ctx* ctx, const double* gamma, double theta, int32_t leaf_size,
                              double* energy, double* dE);
+
+/* Barnes-Hut energy and differential on the tree of the context's last
+ * rc_bh_differential (or Barnes-Hut rc_step), re-fitted to gamma instead of
+ * built anew: the nodes keep their edges and only their centres, lengths,
+ * mean tangents and radii are recomputed (one launch), as the paper suggests
+ * for small time steps (Limitations and Conclusion); the admissibility test reads the re-fitted
+ * radii, so the result is a valid Barnes-Hut sum whose clusters are looser
+ * the further gamma is from the curve the tree was built for.  Same
+ * arguments, outputs and theta range as rc_bh_differential; RC_ERR_ARG when
+ * no tree has been built on the context. */
+rc_status rc_bh_refit_differential(rc_ctx* ctx, const double* gamma, double theta, double* energy, double* dE);
 
 /* Work of the last rc_bh_differential: cluster (far-field) interactions and
  * edge pairs visited in leaves (near field, excluded pairs included), the

@@ -34,7 +34,8 @@ EXPORTED = [
     "rc_constraint_values",
     "rc_constraint_count", "rc_project",
     "rc_sobolev_gradient",
-    "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_bh_last_work", "rc_midpoint_differential",
+    "rc_line_search_step", "rc_step", "rc_bh_differential", "rc_bh_refit_differential", "rc_bh_last_work",
+    "rc_midpoint_differential",
     "rc_profile_enable", "rc_profile_read", "rc_lowp_assemble", "rc_lowp_apply", "rc_set_obstacle",
     "rc_set_penalties", "rc_set_surface_potential",
     "rc_create_batch", "rc_batch_size", "rc_batch_energies", "rc_batch_tiling", "rc_default_batch_opts",
@@ -75,7 +76,8 @@ class BatchOpts(C.Structure):
 class LsOpts(C.Structure):
     _fields_ = [("c_armijo", C.c_double), ("shrink", C.c_double), ("tau0", C.c_double),
                 ("max_backtracks", C.c_int32), ("max_proj_iter", C.c_int32), ("proj_tol", C.c_double),
-                ("proj_solve_tol", C.c_double), ("ccd", C.c_int32), ("bh_theta", C.c_double)]
+                ("proj_solve_tol", C.c_double), ("ccd", C.c_int32), ("bh_theta", C.c_double),
+                ("bh_refit", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -127,6 +129,7 @@ def load():
                                       C.POINTER(Stats)]),
         "rc_step": (I32, [P, P, C.POINTER(SolveOpts), C.POINTER(LsOpts), C.POINTER(Stats)]),
         "rc_bh_differential": (I32, [P, P, D, I32, P, P]),
+        "rc_bh_refit_differential": (I32, [P, P, D, P, P]),
         "rc_midpoint_differential": (I32, [P, P, P, P]),
         "rc_bh_last_work": (I32, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(I32), C.POINTER(I32)]),
         "rc_profile_enable": (I32, [P, I32]),
@@ -398,6 +401,10 @@ class Context:
     def rc_bh_differential(self, gamma, theta, leaf_size, energy, dE):
         _check(load().rc_bh_differential(self.h, self._v(gamma, "gamma"), float(theta), int(leaf_size),
                                          _ptr(energy, (1,), self._f64, "energy"), self._v(dE, "dE")))
+
+    def rc_bh_refit_differential(self, gamma, theta, energy, dE):
+        _check(load().rc_bh_refit_differential(self.h, self._v(gamma, "gamma"), float(theta),
+                                               _ptr(energy, (1,), self._f64, "energy"), self._v(dE, "dE")))
 
     def rc_midpoint_differential(self, gamma, energy, dE):
         _check(load().rc_midpoint_differential(self.h, self._v(gamma, "gamma"),

@@ -118,6 +118,7 @@ void rc_default_ls_opts(rc_ls_opts* o) {
   o->proj_solve_tol = 1e-3;
   o->ccd = 0;
   o->bh_theta = 0.0;
+  o->bh_refit = 0;
 }
 
 const char* rc_last_error(void) { return rc::last_error(); }
@@ -700,6 +701,23 @@ extern "C" rc_status rc_bh_differential(rc_ctx* c, const double* gamma, double t
   }
   RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));
   return launch_bh(c->curve, c->bvh, c->alpha, c->beta, theta, leaf_size, energy, dE, c->stream);
+}
+
+extern "C" rc_status rc_bh_refit_differential(rc_ctx* c, const double* gamma, double theta, double* energy,
+                                              double* dE) {
+  RC_TRY(check_ctx(c));
+  RC_TRY(no_batch(c, "rc_bh_refit_differential"));
+  RC_TRY(check_ptrs({gamma, dE}));
+  if (!(theta > 0.0) || !(theta < 0.5)) {
+    set_error("rc_bh_refit_differential: theta must lie in (0, 0.5)");
+    return RC_ERR_ARG;
+  }
+  if (c->bvh.n_nodes <= 0) {
+    set_error("rc_bh_refit_differential: no Barnes-Hut tree built on this context yet");
+    return RC_ERR_ARG;
+  }
+  RC_TRY(launch_geometry(c->curve, gamma, RC_F32, c->stream));
+  return launch_bh(c->curve, c->bvh, c->alpha, c->beta, theta, 0, energy, dE, c->stream, true);
 }
 
 extern "C" rc_status rc_bh_last_work(rc_ctx* c, int64_t* far_pairs, int64_t* near_pairs, int32_t* nodes,

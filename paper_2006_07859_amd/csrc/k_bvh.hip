@@ -38,7 +38,7 @@ constexpr int kStack = 64;
 // whose mean size is at least kBigNode, in chunks of kBigChunk positions
 constexpr int kBigMaxNodes = 1024, kBigNode = 2048, kBigChunk = 4096, kBigWords = 640;
 
-// tangent-points, SoA [6][nE]: T (3) then midpoint x (3)
+// tangent-points, SoA [6][nE]: T (3) then midpoint x (3); perm (when given) reset to the identity
 __global__ void k_tangent_points(const V4<float>* __restrict__ GA, const V4<float>* __restrict__ GB,
                                  const V4<float>* __restrict__ GT, int nE, float* __restrict__ pts,
                                  int* __restrict__ perm) {
@@ -51,7 +51,7 @@ __global__ void k_tangent_points(const V4<float>* __restrict__ GA, const V4<floa
   pts[3 * (size_t)nE + I] = 0.5f * (a.x + b.x);
   pts[4 * (size_t)nE + I] = 0.5f * (a.y + b.y);
   pts[5 * (size_t)nE + I] = 0.5f * (a.z + b.z);
-  perm[I] = I;
+  if (perm) perm[I] = I;
 }
 
 __device__ __forceinline__ float block_min(float v, float* sm) {
@@ -874,14 +874,34 @@ rc_status build_bvh(const Curve& c, Bvh& bvh, int leaf, hipStream_t s) {
   return RC_OK;
 }
 
+// Re-fit (the remark of the paper's conclusion on small time steps): the tree of the last build
+// keeps its nodes and their edge sets, and only the node data (centre, length, mean tangent, radii)
+// are recomputed from the current edges, in one launch; the admissibility test then reads the
+// re-fitted radii, so the traversal stays valid, and its clusters only grow looser as the curve
+// moves away from the built one.
+rc_status refit_bvh(const Curve& c, Bvh& bvh, hipStream_t s) {
+  const int nE = c.nE;
+  if (bvh.n_nodes <= 0 || bvh.nE != nE) {
+    set_error("BVH re-fit: no tree built for this curve");
+    return RC_ERR_ARG;
+  }
+  hipLaunchKernelGGL(k_tangent_points, dim3(cdiv(nE, 256)), dim3(256), 0, s, c.gf.a, c.gf.b, c.gf.t, nE, bvh.pts,
+                     (int*)nullptr);
+  hipLaunchKernelGGL(k_bvh_props, dim3(bvh.n_nodes), dim3(kBvhThreads), 0, s, bvh.pts, c.gf.a, nE, bvh.node,
+                     bvh.perm, bvh.na, bvh.nb, bvh.nr);
+  RC_HIP(hipGetLastError());
+  return RC_OK;
+}
+
 rc_status launch_bh(const Curve& c, Bvh& bvh, double alpha, double beta, double theta, int leaf, double* energy,
-                    double* dE, hipStream_t s) {
+                    double* dE, hipStream_t s, bool refit) {
   const int nE = c.nE;
   if (c.max_degree > 4) {
     set_error("Barnes-Hut needs vertex degree <= 4 (a target keeps at most 6 neighbouring edges)");
     return RC_ERR_UNSUPPORTED;
   }
-  RC_TRY(build_bvh(c, bvh, leaf, s));
+  if (refit) RC_TRY(refit_bvh(c, bvh, s));
+  else RC_TRY(build_bvh(c, bvh, leaf, s));
   RC_HIP(hipMemsetAsync(bvh.work, 0, sizeof(unsigned long long) * 2, s));
   const float ha = (float)(0.5 * alpha), hb = (float)(0.5 * beta), bb = (float)beta, th = (float)theta;
   dim3 g(cdiv(nE, 256)), b(256);

@@ -323,7 +323,7 @@ rc_status build_bvh(const Curve& c, Bvh& bvh, int leaf, hipStream_t s);
 constexpr int kStepBhLeaf = 32;  // leaf size of the Barnes-Hut evaluations inside rc_step
 // Barnes-Hut energy and differential in FP32 (needs the FP32 geometry).
 rc_status launch_bh(const Curve& c, Bvh& bvh, double alpha, double beta, double theta, int leaf, double* energy,
-                    double* dE, hipStream_t s);
+                    double* dE, hipStream_t s, bool refit = false);
 
 // Per-edge sums Wq, P0 of the operator kernel into edge_out slots 0 and 1
 // (they do not depend on the vector the operator is applied to).

@@ -1765,7 +1765,8 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
     if (ok) {
       RC_TRY(load_geometry(c, c->trial));
       if (ls.bh_theta > 0.0)  // the Barnes-Hut energy (its differential goes to the free PCG buffer q)
-        RC_TRY(launch_bh(c->curve, c->bvh, c->alpha, c->beta, ls.bh_theta, kStepBhLeaf, c->scal + 18, c->q, s));
+        RC_TRY(launch_bh(c->curve, c->bvh, c->alpha, c->beta, ls.bh_theta, kStepBhLeaf, c->scal + 18, c->q, s,
+                         ls.bh_refit != 0 && c->bvh.n_nodes > 0));
       else
         RC_TRY(launch_tpe(c->curve, c->alpha, c->beta, c->dtype, false, c->scal + 18, nullptr, s));
       double E1;

@@ -79,3 +79,38 @@ def test_bh_full_size_sampled(lib):
         ref = sum(dI[k, 0 if e[I, 0] == v else 1] for k, I in enumerate(inc))
         assert np.linalg.norm(G[v] - ref) < 5e-2 * np.linalg.norm(ref)
     assert np.isfinite(E) and E > 0
+
+
+def test_bh_refit(lib):
+    """Re-fitting the tree of the last build to a moved curve: with theta -> 0 the re-fitted
+    traversal is the exact midpoint sum at the moved curve; at theta = 0.25 its error stays
+    close to that of a tree built for the moved curve; without a tree the call is refused."""
+    from paper_2006_07859_amd import RC_F32, Context, RcError
+
+    n = 3000
+    banner(f"BH re-fit fourier{n}")
+    g, e, _ = gen.fourier_knot(n, seed=5)
+    g = gen.round_to_f32(g)
+    ell = np.linalg.norm(g[e[:, 1]] - g[e[:, 0]], axis=1).mean()
+    t = np.linspace(0.0, 2.0 * np.pi, n, endpoint=False)
+    move = 0.5 * ell * np.stack([np.sin(3 * t), np.cos(2 * t), np.sin(5 * t + 1.0)], 1)
+    g2 = gen.round_to_f32(g + move)
+    E_ref, G_ref = tpe.midpoint_differential(g2, e, 2.0, 4.5)
+    ctx = Context(n, e, 2.0, 4.5, RC_F32)
+    E, dE = zeros(1), zeros(n, 3)
+    with pytest.raises(RcError):
+        ctx.rc_bh_refit_differential(dev(g2), 0.25, E, dE)
+    ctx.rc_bh_differential(dev(g), 1e-6, 32, E, dE)
+    ctx.rc_bh_refit_differential(dev(g2), 1e-6, E, dE)
+    assert ctx.rc_bh_last_work()["far"] == 0
+    assert host(E)[0] == pytest.approx(E_ref, rel=2e-5)
+    assert relnorm(host(dE), G_ref) < 2e-4
+    ctx.rc_bh_differential(dev(g), 0.25, 32, E, dE)
+    ctx.rc_bh_refit_differential(dev(g2), 0.25, E, dE)
+    err_refit = (abs(host(E)[0] - E_ref) / E_ref, relnorm(host(dE), G_ref))
+    E_b, G_b, _ = run_bh(g2, e, 2.0, 4.5, 0.25)
+    err_build = (abs(E_b - E_ref) / E_ref, relnorm(G_b, G_ref))
+    print(f"  theta 0.25 re-fit error {err_refit}, rebuilt {err_build}")
+    assert err_refit[0] < 1e-2 and err_refit[1] < 5e-2
+    assert err_refit[1] < 2.0 * err_build[1] + 1e-3
+    ctx.close()
