@@ -1059,6 +1059,71 @@ __device__ __forceinline__ void proj_prep_operand(const ProjData& d, int v, bool
 // for vertex v (the body of k_apply_CT_z); val receives out_v (xacc_v when prep_x).
 // yb, U: the border solution and the reduced boundary values (global memory,
 // or LDS in the fused launch).
+// The loads of the last step that do not depend on the border and reduced
+// solves, for a packed vertex: issued at the start of the fused launch so
+// that their latency overlaps those solves (prev and in may alias out: every
+// entry is read by its own thread before that thread writes it).
+struct CtPre {
+  ProjVert pv;
+  double g[2], V[2], W[2], Z[2][kProjMaxBorder], rows[kProjMaxBorder][3], in[3];
+};
+
+__device__ __forceinline__ void ct_prefetch(const ProjData& d, int v, const double* __restrict__ in, CtPre& p) {
+  const int np = d.np, nb = d.nb;
+  p.pv = d.pvert[v];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int pr = p.pv.row[q];
+    if (pr < 0) continue;
+    p.g[q] = d.g[pr];
+    p.V[q] = d.V[pr];
+    p.W[q] = d.W[pr];
+#pragma unroll
+    for (int r = 0; r < kProjMaxBorder; ++r)
+      if (r < nb) p.Z[q][r] = d.Z[(size_t)r * np + pr];
+  }
+#pragma unroll
+  for (int r = 0; r < kProjMaxBorder; ++r)
+    if (r < nb)
+      for (int cc = 0; cc < 3; ++cc) p.rows[r][cc] = d.rows[((size_t)r * d.nV + v) * 3 + cc];
+  for (int cc = 0; cc < 3; ++cc) p.in[cc] = in[3 * v + cc];
+}
+
+__device__ __forceinline__ void ct_store(const ProjData& d, int v, double (&res)[3], double* __restrict__ out,
+                                         double (&val)[3]);
+
+// apply_CT_z_vertex on prefetched loads (the same arithmetic in the same order)
+__device__ __forceinline__ void ct_finish(const ProjData& d, int v, const CtPre& p, double* __restrict__ out,
+                                          double (&val)[3], const double* yb, const double* U) {
+  const int nb = d.nb;
+  const TriBlocks& L = d.tri;
+  double ybr[kProjMaxBorder];
+#pragma unroll
+  for (int r = 0; r < kProjMaxBorder; ++r) ybr[r] = r < nb ? yb[r] : 0.0;
+  double acc[3] = {0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int pr = p.pv.row[q];
+    if (pr < 0) continue;
+    double y = p.g[q];
+    const int qb = pr / L.S;
+    if (qb < L.B - 1) y -= p.V[q] * U[2 * qb + 1];
+    if (qb > 0) y -= p.W[q] * U[2 * (qb - 1)];
+#pragma unroll
+    for (int r = 0; r < kProjMaxBorder; ++r)
+      if (r < nb) y -= p.Z[q][r] * ybr[r];
+    acc[0] += p.pv.c[q][0] * y;
+    acc[1] += p.pv.c[q][1] * y;
+    acc[2] += p.pv.c[q][2] * y;
+  }
+#pragma unroll
+  for (int r = 0; r < kProjMaxBorder; ++r)
+    if (r < nb)
+      for (int cc = 0; cc < 3; ++cc) acc[cc] += ybr[r] * p.rows[r][cc];
+  double res[3] = {p.in[0] - acc[0], p.in[1] - acc[1], p.in[2] - acc[2]};
+  ct_store(d, v, res, out, val);
+}
+
 __device__ __forceinline__ void apply_CT_z_vertex(const ProjData& d, int v, const double* __restrict__ in,
                                                   double* __restrict__ out, double (&val)[3], const double* yb,
                                                   const double* U) {
@@ -1100,6 +1165,12 @@ __device__ __forceinline__ void apply_CT_z_vertex(const ProjData& d, int v, cons
     if (r < nb)
       for (int cc = 0; cc < 3; ++cc) acc[cc] += ybr[r] * d.rows[((size_t)r * d.nV + v) * 3 + cc];
   double res[3] = {in[3 * v] - acc[0], in[3 * v + 1] - acc[1], in[3 * v + 2] - acc[2]};
+  ct_store(d, v, res, out, val);
+}
+
+// out_v = beta prev_v + scale W_v res (and xacc) from res = in_v - (C^T y)_v
+__device__ __forceinline__ void ct_store(const ProjData& d, int v, double (&res)[3], double* __restrict__ out,
+                                         double (&val)[3]) {
   double sw = d.scale;
   if (d.nrm)  // W_v (in - C^T y) with the normal part
     proj_w_apply(d, v, res[0], res[1], res[2]);
@@ -1132,6 +1203,8 @@ __global__ __launch_bounds__(256) void k_apply_CT_z(const ProjData d, const doub
 // border (yb) and applies M^-1 to the block-boundary values (U) itself, in
 // the order k_proj_solve uses, into LDS, then applies C^T y to its vertices.
 constexpr int kFuseMaxNr = 128;
+constexpr int kPrefetchMaxV = 65536;  // 256 workgroups of 256 vertices
+template <bool PRE>
 __global__ __launch_bounds__(256) void k_solve_apply_CT_z(const ProjData d, int nblk, const double* __restrict__ in,
                                                           double* __restrict__ out) {
   __shared__ double tot[kProjSlots], ybs[kProjMaxBorder];
@@ -1139,6 +1212,10 @@ __global__ __launch_bounds__(256) void k_solve_apply_CT_z(const ProjData d, int 
   const int t = threadIdx.x, nb = d.nb;
   const TriBlocks& L = d.tri;
   const int nr = L.nr;
+  const int v = blockIdx.x * blockDim.x + t;
+  const bool vert = v < d.nV;
+  CtPre pre;
+  if (PRE && vert && d.pvert) ct_prefetch(d, v, in, pre);
   {  // slot q = t / 16 summed over the workgroups of k_proj_rows by 16 lanes
     const int q = t / 16, sgm = t % 16;
     double v = 0.0;
@@ -1179,19 +1256,25 @@ __global__ __launch_bounds__(256) void k_solve_apply_CT_z(const ProjData d, int 
     if (h == 0 && i < nr) Us[i] = half_sum[t] + half_sum[t + kHalf];
   }
   __syncthreads();
-  const int v = blockIdx.x * blockDim.x + t;
-  const bool vert = v < d.nV;
   double val[3] = {0.0, 0.0, 0.0};
-  if (vert) apply_CT_z_vertex(d, v, in, out, val, ybs, Us);
+  if (vert) {
+    if (PRE && d.pvert) ct_finish(d, v, pre, out, val, ybs, Us);
+    else apply_CT_z_vertex(d, v, in, out, val, ybs, Us);
+  }
   if (d.pp) proj_prep_operand<256>(d, v, vert, val);
 }
 
 // The last step of k_proj_small for vertex t; val receives out_t (xacc_t when
 // prep_x); pin and ain hold prev_t and xacc_t, loaded before the barriers.
+// Z of the vertex's path rows for the first kSmallPreB border rows, loaded
+// before the barriers of k_proj_small (the rest is loaded at the end)
+constexpr int kSmallPreB = 4;
+
 __device__ __forceinline__ void proj_small_vertex(const ProjData& d, int t, double* __restrict__ out,
                                                   const ProjVert& pv, double w_t, double x0, double x1, double x2,
                                                   const double* yps, const double* ybs, const double (&pin)[3],
-                                                  const double (&ain)[3], double (&val)[3]) {
+                                                  const double (&ain)[3], const double (&zp)[2][kSmallPreB],
+                                                  double (&val)[3]) {
   const int np = d.np, nV = d.nV, nb = d.nb;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
@@ -1201,7 +1284,7 @@ __device__ __forceinline__ void proj_small_vertex(const ProjData& d, int t, doub
     double y = yps[p];
 #pragma unroll
     for (int r = 0; r < kProjMaxBorder; ++r)
-      if (r < nb) y -= d.Z[(size_t)r * np + p] * ybs[r];
+      if (r < nb) y -= (r < kSmallPreB ? zp[q][r < kSmallPreB ? r : 0] : d.Z[(size_t)r * np + p]) * ybs[r];
     a0 += pv.c[q][0] * y;
     a1 += pv.c[q][1] * y;
     a2 += pv.c[q][2] * y;
@@ -1268,6 +1351,12 @@ __global__ __launch_bounds__(kTriThreads) void k_proj_small(const ProjData d, co
   ProjVert pv;
   pv.row[0] = pv.row[1] = -1;
   if (vert) pv = d.pvert[t];
+  double zp[2][kSmallPreB];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int r = 0; r < kSmallPreB; ++r)
+      zp[q][r] = (pv.row[q] >= 0 && r < nb) ? d.Z[(size_t)r * np + pv.row[q]] : 0.0;
   // the last step's inputs that do not depend on x, loaded ahead of the barriers
   double pin[3] = {0.0, 0.0, 0.0}, ain[3] = {0.0, 0.0, 0.0};
   if (vert) {
@@ -1350,7 +1439,7 @@ __global__ __launch_bounds__(kTriThreads) void k_proj_small(const ProjData d, co
   }
   __syncthreads();
   double val[3] = {0.0, 0.0, 0.0};
-  if (vert) proj_small_vertex(d, t, out, pv, w_t, x0, x1, x2, yps, ybs, pin, ain, val);
+  if (vert) proj_small_vertex(d, t, out, pv, w_t, x0, x1, x2, yps, ybs, pin, ain, zp, val);
   if (d.pp) proj_prep_operand<kTriThreads>(d, t, vert, val);
 }
 
@@ -1364,7 +1453,11 @@ void cons_project_fused(const ProjData& d, const double* in, double* out, hipStr
   const int nblk = std::max(d.np > 0 ? d.tri.B : 1, std::min(64, cdiv(d.nV, kSpThreads)));
   hipLaunchKernelGGL(k_proj_rows, dim3(nblk), dim3(kSpThreads), 0, s, d, in);
   if (d.tri.nr <= kFuseMaxNr) {
-    hipLaunchKernelGGL(k_solve_apply_CT_z, dim3(cdiv(d.nV, 256)), dim3(256), 0, s, d, nblk, in, out);
+    // the prefetching variant holds more registers: for grids of one wave of workgroups over the chip
+    if (d.nV <= kPrefetchMaxV)
+      hipLaunchKernelGGL(k_solve_apply_CT_z<true>, dim3(cdiv(d.nV, 256)), dim3(256), 0, s, d, nblk, in, out);
+    else
+      hipLaunchKernelGGL(k_solve_apply_CT_z<false>, dim3(cdiv(d.nV, 256)), dim3(256), 0, s, d, nblk, in, out);
     return;
   }
   hipLaunchKernelGGL(k_proj_solve, dim3(1), dim3(kSpThreads), 0, s, d, nblk);
