@@ -335,7 +335,8 @@ void Curve::release() {
   vp = false;
   vinfo = nullptr;
   vg[0] = vg[1] = vg[2] = nullptr;
-  vpart = vout = nullptr;
+  vpart = nullptr;
+  vout = nullptr;
   inst_voff = inst_eoff = inst_of_edge = inst_of_vertex = nch_e = counter = nullptr;
   items = nullptr;
   n_inst = n_items = 0;

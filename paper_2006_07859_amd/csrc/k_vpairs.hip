@@ -38,6 +38,8 @@ namespace rc {
 
 static inline int vp_cdiv(int a, int b) { return (a + b - 1) / b; }
 
+constexpr int kBandLanes = 16;  // lanes per target edge of the FP64 near band (a power of two, <= 64)
+
 // Same chain and at most kBand steps apart (cyclically on a loop).
 __device__ __forceinline__ bool vert_near(int4 a, int4 b) {
   if (a.x != b.x) return false;
@@ -74,12 +76,13 @@ __global__ void k_vgeom(const double* __restrict__ gamma, const V4<double>* __re
 // target v, the workgroup's 256 targets sweep the source range of chunk
 // blockIdx.y staged in LDS tiles of 256 vertices, FP32 sums folded into FP64
 // every kSub sources.  Slots: E, G1 (3), H (3), G3 (3), A0 (3), A1 (3), L,
-// written to part[chunk][slot][v].
+// written to part[chunk][slot][v] rounded to FP32 (a chunk's sum carries the
+// rounding of its FP32 sub-sums already; the chunks are added in FP64).
 template <int EC, bool GRAD>
 __global__ __launch_bounds__(kTile) void k_vp_pairs(const V4<float>* __restrict__ P, const V4<float>* __restrict__ U0,
                                                     const V4<float>* __restrict__ U1, const int4* __restrict__ vinfo,
                                                     int nV, int src_per_chunk, float half_beta, float beta,
-                                                    double* __restrict__ part) {
+                                                    float* __restrict__ part) {
   __shared__ V4<float> sP[kTile], sU0[kTile], sU1[kTile];
   __shared__ int4 sC[kTile];
   __shared__ int4 sRed[2][kTile / 64];
@@ -177,17 +180,19 @@ __global__ __launch_bounds__(kTile) void k_vp_pairs(const V4<float>* __restrict_
     }
   }
   if (act) {
-    double* out = part + (size_t)blockIdx.y * NS * nV + v;
+    float* out = part + (size_t)blockIdx.y * NS * nV + v;
 #pragma unroll
-    for (int k = 0; k < NS; ++k) out[(size_t)k * nV] = acc[k];
+    for (int k = 0; k < NS; ++k) out[(size_t)k * nV] = (float)acc[k];
   }
 }
 
 // FP64 near band of the vertex-pair form: for target edge I, every edge J of
 // its chain at most kBand + 1 steps away, in the edge-pair form with the
 // exact shared-vertex exclusion, keeping only the vertex pairs at most kBand
-// steps apart (the ones the vertex-pair kernel masks).  Four lanes per target
-// edge, summed across the lanes in a fixed order; writes chunk 0 of part.
+// steps apart (the ones the vertex-pair kernel masks).  kBandLanes lanes per
+// target edge (about 4 of its 2 kBand + 3 band edges each, so that 16 waves a
+// compute unit hide the FP64 latency), summed across the lanes by a fixed
+// butterfly; writes chunk 0 of part.
 template <int EC, bool GRAD>
 __global__ __launch_bounds__(256) void k_tpe_band_v(const V4<double>* __restrict__ GA,
                                                     const V4<double>* __restrict__ GT, const int2* __restrict__ edges,
@@ -195,7 +200,7 @@ __global__ __launch_bounds__(256) void k_tpe_band_v(const V4<double>* __restrict
                                                     const int4* __restrict__ vinfo, int nE, double half_beta,
                                                     double beta, double* __restrict__ part) {
   const int tg = blockIdx.x * blockDim.x + threadIdx.x;
-  const int I = tg / 4, sub = tg % 4;
+  const int I = tg / kBandLanes, sub = tg % kBandLanes;
   const bool valid = I < nE;
   double E = 0, S = 0, G1x = 0, G1y = 0, G1z = 0, G2x = 0, G2y = 0, G2z = 0;
   double Gt1 = 0, Gt2 = 0, Hx = 0, Hy = 0, Hz = 0;
@@ -219,7 +224,7 @@ __global__ __launch_bounds__(256) void k_tpe_band_v(const V4<double>* __restrict
       q0 = max(0, ci.y - W);
       q1 = min(m - 1, ci.y + W);
     }
-    for (int q = q0 + sub; q <= q1; q += 4) {
+    for (int q = q0 + sub; q <= q1; q += kBandLanes) {
       const int qq = ((q % m) + m) % m;
       const int J = chain_edge[ci.x + qq];
       const int2 ej = edges[J];
@@ -234,14 +239,15 @@ __global__ __launch_bounds__(256) void k_tpe_band_v(const V4<double>* __restrict
                                                   Hy, Hz, m4);
     }
   }
-  auto red4 = [](double v) {  // (v0 + v1) + (v2 + v3) on every lane of the group
-    v += __shfl_xor(v, 1, 64);
-    return v + __shfl_xor(v, 2, 64);
+  auto red = [](double v) {  // butterfly over the group: the same sum, in the same order, on every lane
+#pragma unroll
+    for (int o = 1; o < kBandLanes; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
   };
   constexpr int NS = GRAD ? kTpeSlots : 1;
   double v[kTpeSlots] = {E, S, G1x, G1y, G1z, G2x, G2y, G2z, Gt1, Gt2, Hx, Hy, Hz, 0.0};
 #pragma unroll
-  for (int k = 0; k < NS; ++k) v[k] = red4(v[k]);
+  for (int k = 0; k < NS; ++k) v[k] = red(v[k]);
   if (GRAD) v[13] = t.x * v[10] + t.y * v[11] + t.z * v[12];  // T.H: H holds multiples of T
   if (!valid || sub != 0) return;
   double* out = part + I;
@@ -268,45 +274,45 @@ __device__ __forceinline__ double vertex_u(const V4<double>* __restrict__ GA, co
   return lam;
 }
 
-// Per vertex: sums the chunks (fixed order) and writes
+// Per vertex: sums the chunks and writes
 // vout[v] = (E_v, direct gradient (3), dE/du_0 (3), dE/du_1 (3), dE/dLambda_v, 0).
-// The per-chunk partial sums of every slot, added in chunk order into chunk 0
-// (a thread per (slot, vertex), eight loads in flight), so that the finalize
-// reads one chunk: the same sums in the same order as a serial pass.
-__global__ void k_vp_reduce(double* __restrict__ part, int nchunk, int NS, int nV) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= NS * nV) return;
-  const int k = i / nV, v = i % nV;
-  const size_t stride = (size_t)NS * nV;
-  const double* p = part + (size_t)k * nV + v;
-  double a = 0.0;
-  int c = 0;
-  for (; c + 8 <= nchunk; c += 8) {
-    double t[8];
+// A thread per (slot, vertex) adds the slot's chunk partials in chunk order in
+// FP64 (eight loads in flight; kVpSumV consecutive vertices make one 128-byte
+// line per slot and chunk), then one thread per vertex finishes from LDS.
+constexpr int kVpSumV = 32;
+__global__ __launch_bounds__(kVpSumV* kVpSlots) void k_vp_sum(const float* __restrict__ part, int nchunk, int NS,
+                                                              int nV, double beta, const V4<double>* __restrict__ GA,
+                                                              const V4<double>* __restrict__ GT,
+                                                              const int* __restrict__ inc_off,
+                                                              const int* __restrict__ inc, double* __restrict__ vout,
+                                                              unsigned* __restrict__ status) {
+  __shared__ double sm[kVpSlots][kVpSumV];
+  const int j = threadIdx.x % kVpSumV, k = threadIdx.x / kVpSumV;  // k < NS (blockDim = kVpSumV NS)
+  const int v = blockIdx.x * kVpSumV + j;
+  if (v < nV) {
+    const size_t stride = (size_t)NS * nV;
+    const float* p = part + (size_t)k * nV + v;
+    double a = 0.0;
+    int c = 0;
+    for (; c + 8 <= nchunk; c += 8) {
+      float t[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = p[(size_t)(c + u) * stride];
+      for (int u = 0; u < 8; ++u) t[u] = p[(size_t)(c + u) * stride];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a += t[u];
+      for (int u = 0; u < 8; ++u) a += (double)t[u];
+    }
+    for (; c < nchunk; ++c) a += (double)p[(size_t)c * stride];
+    sm[k][j] = a;
   }
-  for (; c < nchunk; ++c) a += p[(size_t)c * stride];
-  part[(size_t)k * nV + v] = a;
-}
-
-__global__ void k_vp_finalize(const double* __restrict__ part, int nchunk, int nV, int grad, double beta,
-                              const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GT,
-                              const int* __restrict__ inc_off, const int* __restrict__ inc,
-                              double* __restrict__ vout, unsigned* __restrict__ status) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nV) return;
-  const int NS = grad ? kVpSlots : 1;
+  __syncthreads();
+  if (k != 0 || v >= nV) return;
+  const bool grad = NS > 1;
   double s[kVpSlots];
   bool fin = true;
-  for (int k = 0; k < kVpSlots; ++k) {
-    double a = 0.0;
-    if (k < NS)
-      for (int c = 0; c < nchunk; ++c) a += part[((size_t)c * NS + k) * nV + v];
-    s[k] = a;
-    fin &= isfinite(a);
+#pragma unroll
+  for (int q = 0; q < kVpSlots; ++q) {
+    s[q] = q < NS ? sm[q][j] : 0.0;
+    fin &= isfinite(s[q]);
   }
   if (!fin) latch(status, kFlagPairOverflow);
   double* o = vout + (size_t)kVpOut * v;
@@ -317,11 +323,11 @@ __global__ void k_vp_finalize(const double* __restrict__ part, int nchunk, int n
   const double G1[3] = {s[1], s[2], s[3]}, H[3] = {s[4], s[5], s[6]}, G3[3] = {s[7], s[8], s[9]};
   const double c0 = u[0][0] * G1[0] + u[0][1] * G1[1] + u[0][2] * G1[2];
   const double c1 = u[1][0] * G1[0] + u[1][1] * G1[1] + u[1][2] * G1[2];
-  for (int k = 0; k < 3; ++k) {
-    const double MG1 = lam * G1[k] - u[0][k] * c0 - u[1][k] * c1;
-    o[1 + k] = 0.25 * (2.0 * MG1 + 2.0 * lam * (G1[k] - H[k]) - beta * G3[k]);
-    o[4 + k] = -0.5 * s[10 + k];
-    o[7 + k] = -0.5 * s[13 + k];
+  for (int q = 0; q < 3; ++q) {
+    const double MG1 = lam * G1[q] - u[0][q] * c0 - u[1][q] * c1;
+    o[1 + q] = 0.25 * (2.0 * MG1 + 2.0 * lam * (G1[q] - H[q]) - beta * G3[q]);
+    o[4 + q] = -0.5 * s[10 + q];
+    o[7 + q] = -0.5 * s[13 + q];
   }
   o[10] = 0.25 * s[16];
   o[11] = 0.0;
@@ -396,7 +402,7 @@ static void run_vp(const Curve& c, double beta, hipStream_t s) {
                      (const V4<float>*)c.vg[0], (const V4<float>*)c.vg[1], (const V4<float>*)c.vg[2],
                      (const int4*)c.vinfo, c.nV, c.vsrc_per_chunk, (float)(0.5 * beta), (float)beta, c.vpart);
   if (timed) c.timer->mark(c.timer->tpe, s);
-  hipLaunchKernelGGL((k_tpe_band_v<EC, GRAD>), dim3(vp_cdiv(c.nE, 64)), dim3(256), 0, s, (const V4<double>*)c.gd.a,
+  hipLaunchKernelGGL((k_tpe_band_v<EC, GRAD>), dim3(vp_cdiv(c.nE, 256 / kBandLanes)), dim3(256), 0, s, (const V4<double>*)c.gd.a,
                      (const V4<double>*)c.gd.t, (const int2*)c.edges, (const int4*)c.cinfo,
                      (const int*)c.chain_edge, (const int4*)c.vinfo, c.nE, 0.5 * beta, beta, c.part);
 }
@@ -422,13 +428,8 @@ rc_status launch_tpe_vp_pairs(const Curve& c, double beta, bool grad, hipStream_
 
 rc_status launch_tpe_vp_finish(const Curve& c, double beta, bool grad, double* dE, hipStream_t s) {
   const int NS = grad ? kVpSlots : 1;
-  int nch = c.vchunk;
-  if (nch > 1) {
-    hipLaunchKernelGGL(k_vp_reduce, dim3(vp_cdiv(NS * c.nV, 256)), dim3(256), 0, s, c.vpart, nch, NS, c.nV);
-    nch = 1;
-  }
-  hipLaunchKernelGGL(k_vp_finalize, dim3(vp_cdiv(c.nV, 256)), dim3(256), 0, s, (const double*)c.vpart, nch, c.nV,
-                     grad ? 1 : 0, beta, (const V4<double>*)c.gd.a, (const V4<double>*)c.gd.t,
+  hipLaunchKernelGGL(k_vp_sum, dim3(vp_cdiv(c.nV, kVpSumV)), dim3(kVpSumV * NS), 0, s, (const float*)c.vpart,
+                     c.vchunk, NS, c.nV, beta, (const V4<double>*)c.gd.a, (const V4<double>*)c.gd.t,
                      (const int*)c.inc_off, (const int*)c.inc, c.vout, c.status);
   hipLaunchKernelGGL(k_vp_edge, dim3(vp_cdiv(c.nE, 256)), dim3(256), 0, s, (const double*)c.vout,
                      (const int2*)c.edges, (const int*)c.inc_off, (const int*)c.inc, (const V4<double>*)c.gd.a,

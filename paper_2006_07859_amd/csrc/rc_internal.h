@@ -182,12 +182,12 @@ struct Curve {
   // Vertex-pair form of the alpha = 2 energy + differential (chain graphs,
   // FP32; enable_vertex_pairs): per vertex (chain, position, vertex count, is
   // loop), the FP32 vertex geometry (x_v, Lambda_v), u_0, u_1 (sqrt(l) T of
-  // the vertex's incident edges in incidence order), the partial sums
-  // [vchunk][kVpSlots][nV] and the finalised per-vertex values [nV][kVpOut].
+  // the vertex's incident edges in incidence order), the FP32 chunk partial
+  // sums [vchunk][kVpSlots][nV] and the finalised per-vertex values [nV][kVpOut].
   bool vp = false;
   int4* vinfo = nullptr;
   V4<float>* vg[3] = {nullptr, nullptr, nullptr};
-  double* vpart = nullptr;
+  float* vpart = nullptr;
   double* vout = nullptr;
   int vchunk = 1, vsrc_per_chunk = 0;
   rc_status enable_vertex_pairs();
