@@ -34,28 +34,64 @@ ExpCase exp_case(double alpha, double beta) {
 // ---------------------------------------------------------------------------
 // edge geometry: FP64 state -> rounded SoA in the kernel precision
 // ---------------------------------------------------------------------------
-// The FP64 pass (status != null) latches a non-finite coordinate and a
-// zero-length edge (l_I = 0: T_I is undefined, Sec. 4 Notation).
-template <typename R>
+// a_I = (g_i1, l_I), b_I = (g_i2, 0), T_I = (e_I / l_I, 0) in FP64 and, when
+// Af is set, the same values rounded to FP32 (the FP32 pair kernels' copy).
+// When P is set (the vertex-pair form) thread v also writes the FP32 vertex
+// geometry (g_v, Lambda_v), u_0, u_1 (sqrt(l_I) T_I of v's first two incident
+// edges in incidence order), its incident edges recomputed from gamma in the
+// same arithmetic.  A non-finite coordinate and a zero-length edge (l_I = 0:
+// T_I is undefined, Sec. 4 Notation) are latched.
+__device__ __forceinline__ double edge_vector(const double* __restrict__ gamma, int2 e, double (&p)[3],
+                                              double (&q)[3], double (&d)[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    p[k] = gamma[3 * e.x + k];
+    q[k] = gamma[3 * e.y + k];
+    d[k] = q[k] - p[k];
+  }
+  return sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+}
+
 __global__ void k_geometry(const double* __restrict__ gamma, const int2* __restrict__ edges, int nE,
-                           V4<R>* __restrict__ A, V4<R>* __restrict__ B, V4<R>* __restrict__ T,
+                           V4<double>* __restrict__ A, V4<double>* __restrict__ B, V4<double>* __restrict__ T,
+                           V4<float>* __restrict__ Af, V4<float>* __restrict__ Bf, V4<float>* __restrict__ Tf,
+                           const int* __restrict__ inc_off, const int* __restrict__ inc, int nV,
+                           V4<float>* __restrict__ P, V4<float>* __restrict__ U0, V4<float>* __restrict__ U1,
                            unsigned* __restrict__ status) {
-  int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nE) return;
-  int2 e = edges[I];
-  double p0 = gamma[3 * e.x], p1 = gamma[3 * e.x + 1], p2 = gamma[3 * e.x + 2];
-  double q0 = gamma[3 * e.y], q1 = gamma[3 * e.y + 1], q2 = gamma[3 * e.y + 2];
-  double d0 = q0 - p0, d1 = q1 - p1, d2 = q2 - p2;
-  double l = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-  if (status) {
-    const bool fin = isfinite(p0) & isfinite(p1) & isfinite(p2) & isfinite(q0) & isfinite(q1) & isfinite(q2);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nE) {
+    double p[3], q[3], d[3];
+    const double l = edge_vector(gamma, edges[i], p, q, d);
+    const bool fin = isfinite(p[0]) & isfinite(p[1]) & isfinite(p[2]) & isfinite(q[0]) & isfinite(q[1]) &
+                     isfinite(q[2]);
     if (!fin) latch(status, kFlagInputNonfinite);
     else if (!(l > 0.0)) latch(status, kFlagZeroEdge);
+    const double il = 1.0 / l;
+    const double t0 = d[0] * il, t1 = d[1] * il, t2 = d[2] * il;
+    A[i] = V4<double>{p[0], p[1], p[2], l};
+    B[i] = V4<double>{q[0], q[1], q[2], 0.0};
+    T[i] = V4<double>{t0, t1, t2, 0.0};
+    if (Af) {
+      Af[i] = V4<float>{(float)p[0], (float)p[1], (float)p[2], (float)l};
+      Bf[i] = V4<float>{(float)q[0], (float)q[1], (float)q[2], 0.f};
+      Tf[i] = V4<float>{(float)t0, (float)t1, (float)t2, 0.f};
+    }
   }
-  double il = 1.0 / l;
-  A[I] = V4<R>{R(p0), R(p1), R(p2), R(l)};
-  B[I] = V4<R>{R(q0), R(q1), R(q2), R(0)};
-  T[I] = V4<R>{R(d0 * il), R(d1 * il), R(d2 * il), R(0)};
+  if (P && i < nV) {
+    double lam = 0.0, u[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    const int k0 = inc_off[i], k1 = min(inc_off[i + 1], k0 + 2);
+    for (int k = k0; k < k1; ++k) {
+      double p[3], q[3], d[3];
+      const double l = edge_vector(gamma, edges[inc[k] >> 1], p, q, d);
+      const double il = 1.0 / l, sl = sqrt(l);
+      lam += l;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u[k - k0][c] = sl * (d[c] * il);
+    }
+    P[i] = V4<float>{(float)gamma[3 * i], (float)gamma[3 * i + 1], (float)gamma[3 * i + 2], (float)lam};
+    U0[i] = V4<float>{(float)u[0][0], (float)u[0][1], (float)u[0][2], 0.f};
+    U1[i] = V4<float>{(float)u[1][0], (float)u[1][1], (float)u[1][2], 0.f};
+  }
 }
 
 // Chain-near test: edges of the same chain at most kBand apart (cyclically on loops).
@@ -301,12 +337,9 @@ __device__ __forceinline__ void sum_chunks4(const double* __restrict__ part, int
 }
 
 // Sum the chunks and turn the accumulators into per-edge energy and endpoint
-// partials: edge_out[I] = (E_I, dE/dg_i1 (3), dE/dg_i2 (3), -).
+// partials: edge_out[I] = (E_I, dE/dg_i1 (3), dE/dg_i2 (3), -) (tpe_edge_record).
 // Chunks 0 .. n - 1 with n = nch_e[I] (batch) or nchunk, then the near-band
 // chunk `band_chunk` when it is >= 0.  64 edges per workgroup of 256 threads.
-// A non-finite pair sum of an edge with a finite length means that a disjoint
-// pair's kernel overflowed: coincident (or nearly coincident) vertices of
-// disjoint edges, where the energy is infinite (Sec. 4.1); it is latched.
 __global__ __launch_bounds__(256) void k_tpe_finalize(const double* __restrict__ part, int nchunk,
                                                       const int* __restrict__ nch_e, int band_chunk, int nE, int grad,
                                                       const double* __restrict__ gd_a,
@@ -319,23 +352,8 @@ __global__ __launch_bounds__(256) void k_tpe_finalize(const double* __restrict__
   double s[kTpeSlots];
   sum_chunks4<kTpeSlots>(part, nc, band_chunk, NS, nE, I, valid, s);
   if (threadIdx.x >= 64 || !valid) return;
-  const double l = gd_a[4 * I + 3];
-  double* o = edge_out + 8 * (size_t)I;
-  o[0] = l * s[0];
-  bool fin = isfinite(s[0]);
-  if (grad)
-    for (int k = 1; k < kTpeSlots; ++k) fin &= isfinite(s[k]);
-  if (!fin && isfinite(l) && l > 0.0) latch(status, kFlagPairOverflow);
-  if (!grad) return;
-  const double Tx = gd_t[4 * I], Ty = gd_t[4 * I + 1], Tz = gd_t[4 * I + 2];
-  const double S = s[1];
-  const double Hx = s[10] - s[13] * Tx, Hy = s[11] - s[13] * Ty, Hz = s[12] - s[13] * Tz;
-  o[1] = -Tx * S + l * (s[2] - s[8] * Tx) + 2.0 * Hx;
-  o[2] = -Ty * S + l * (s[3] - s[8] * Ty) + 2.0 * Hy;
-  o[3] = -Tz * S + l * (s[4] - s[8] * Tz) + 2.0 * Hz;
-  o[4] = Tx * S + l * (s[5] - s[9] * Tx) - 2.0 * Hx;
-  o[5] = Ty * S + l * (s[6] - s[9] * Ty) - 2.0 * Hy;
-  o[6] = Tz * S + l * (s[7] - s[9] * Tz) - 2.0 * Hz;
+  tpe_edge_record(s, grad != 0, gd_a[4 * I + 3], gd_t[4 * I], gd_t[4 * I + 1], gd_t[4 * I + 2],
+                  edge_out + 8 * (size_t)I, status);
 }
 
 // dE_v = sum over incident (edge, endpoint) of the edge's endpoint partial.
@@ -916,13 +934,13 @@ rc_status launch_penalties(const Curve& c, bool grad, hipStream_t s) {
 }
 
 rc_status launch_geometry(const Curve& c, const double* gamma, rc_dtype prec, hipStream_t s) {
-  dim3 g(cdiv(c.nE, 256)), b(256);
-  if (prec == RC_F32)
-    hipLaunchKernelGGL(k_geometry<float>, g, b, 0, s, gamma, c.edges, c.nE, c.gf.a, c.gf.b, c.gf.t,
-                       (unsigned*)nullptr);
-  // the FP64 copy is always kept: the finalize kernels read l_I and T_I from it
-  hipLaunchKernelGGL(k_geometry<double>, g, b, 0, s, gamma, c.edges, c.nE, c.gd.a, c.gd.b, c.gd.t, c.status);
-  if (c.vp && prec == RC_F32) launch_vertex_geometry(c, gamma, s);
+  // the FP64 copy is always kept (the finalize kernels read l_I and T_I from it), the FP32 one and the
+  // vertex-pair geometry with it in the same launch
+  const bool f32 = prec == RC_F32, vp = f32 && c.vp;
+  const int n = vp ? std::max(c.nE, c.nV) : c.nE;
+  hipLaunchKernelGGL(k_geometry, dim3(cdiv(n, 256)), dim3(256), 0, s, gamma, c.edges, c.nE, c.gd.a, c.gd.b, c.gd.t,
+                     f32 ? c.gf.a : nullptr, f32 ? c.gf.b : nullptr, f32 ? c.gf.t : nullptr, c.inc_off, c.inc, c.nV,
+                     vp ? c.vg[0] : nullptr, vp ? c.vg[1] : nullptr, vp ? c.vg[2] : nullptr, c.status);
   RC_HIP(hipGetLastError());
   return RC_OK;
 }
@@ -980,11 +998,13 @@ rc_status launch_tpe(const Curve& c, double alpha, double beta, rc_dtype prec, b
                      double* energy, double* dE, hipStream_t s) {
   if (c.vp && prec == RC_F32 && alpha == 2.0 && c.n_inst == 0 && !c.obstacle.on) {
     // alpha = 2 chain graph: the vertex-pair form, its FP64 near band in chunk 0
-    RC_TRY(launch_tpe_vp_pairs(c, beta, grad, s));
-    hipLaunchKernelGGL(k_tpe_finalize, dim3(cdiv(c.nE, 64)), dim3(256), 0, s, c.part, 0, (const int*)nullptr, 0,
-                       c.nE, grad ? 1 : 0, (const double*)c.gd.a, (const double*)c.gd.t, c.edge_out, c.status);
-    RC_TRY(launch_tpe_vp_finish(c, beta, grad, dE, s));
-    if (energy) sum_edge_slot(c, 0, energy, s);
+    RC_TRY(launch_tpe_vp_pairs(c, beta, grad, s));  // the near band writes the edge records
+    // without penalties the edge pass also takes the first pass of the total energy (the same sums in the
+    // same order as sum_edge_slot)
+    const bool fold = energy && !c.spot.on && !c.pen.on;
+    RC_TRY(launch_tpe_vp_finish(c, beta, grad, dE, fold ? c.red : nullptr, s));
+    if (fold) hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, c.red, c.red_blocks, energy, c.status);
+    else if (energy) sum_edge_slot(c, 0, energy, s);
     RC_HIP(hipGetLastError());
     return RC_OK;
   }

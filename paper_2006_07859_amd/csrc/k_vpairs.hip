@@ -48,30 +48,6 @@ __device__ __forceinline__ bool vert_near(int4 a, int4 b) {
   return d <= kBand;
 }
 
-// Per-vertex FP32 geometry: (g_v, Lambda_v), u of the first and of the second
-// incident edge (incidence order), from the FP64 edge geometry.
-__global__ void k_vgeom(const double* __restrict__ gamma, const V4<double>* __restrict__ GA,
-                        const V4<double>* __restrict__ GT, const int* __restrict__ inc_off,
-                        const int* __restrict__ inc, int nV, V4<float>* __restrict__ P, V4<float>* __restrict__ U0,
-                        V4<float>* __restrict__ U1) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nV) return;
-  double lam = 0.0, u[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-  const int k0 = inc_off[v], k1 = min(inc_off[v + 1], k0 + 2);
-  for (int k = k0; k < k1; ++k) {
-    const int I = inc[k] >> 1;
-    const V4<double> a = GA[I], t = GT[I];
-    const double sl = sqrt(a.w);
-    lam += a.w;
-    u[k - k0][0] = sl * t.x;
-    u[k - k0][1] = sl * t.y;
-    u[k - k0][2] = sl * t.z;
-  }
-  P[v] = V4<float>{(float)gamma[3 * v], (float)gamma[3 * v + 1], (float)gamma[3 * v + 2], (float)lam};
-  U0[v] = V4<float>{(float)u[0][0], (float)u[0][1], (float)u[0][2], 0.f};
-  U1[v] = V4<float>{(float)u[1][0], (float)u[1][1], (float)u[1][2], 0.f};
-}
-
 // All ordered vertex pairs (v, w) more than kBand steps apart: a thread owns
 // target v, the workgroup's 256 targets sweep the source range of chunk
 // blockIdx.y staged in LDS tiles of 256 vertices, FP32 sums folded into FP64
@@ -192,21 +168,23 @@ __global__ __launch_bounds__(kTile) void k_vp_pairs(const V4<float>* __restrict_
 // steps apart (the ones the vertex-pair kernel masks).  kBandLanes lanes per
 // target edge (about 4 of its 2 kBand + 3 band edges each, so that 16 waves a
 // compute unit hide the FP64 latency), summed across the lanes by a fixed
-// butterfly; writes chunk 0 of part.
+// butterfly; writes the edge's record to edge_out (tpe_edge_record), to which
+// the vertex sums are added later.
 template <int EC, bool GRAD>
 __global__ __launch_bounds__(256) void k_tpe_band_v(const V4<double>* __restrict__ GA,
                                                     const V4<double>* __restrict__ GT, const int2* __restrict__ edges,
                                                     const int4* __restrict__ cinfo, const int* __restrict__ chain_edge,
                                                     const int4* __restrict__ vinfo, int nE, double half_beta,
-                                                    double beta, double* __restrict__ part) {
+                                                    double beta, double* __restrict__ edge_out,
+                                                    unsigned* __restrict__ status) {
   const int tg = blockIdx.x * blockDim.x + threadIdx.x;
   const int I = tg / kBandLanes, sub = tg % kBandLanes;
   const bool valid = I < nE;
   double E = 0, S = 0, G1x = 0, G1y = 0, G1z = 0, G2x = 0, G2y = 0, G2z = 0;
   double Gt1 = 0, Gt2 = 0, Hx = 0, Hy = 0, Hz = 0;
-  V4<double> t{0, 0, 0, 0};
+  V4<double> a{0, 0, 0, 0}, t{0, 0, 0, 0};
   if (valid) {
-    const V4<double> a = GA[I];
+    a = GA[I];
     t = GT[I];
     const int2 ei = edges[I];
     const int4 ci = cinfo[I];
@@ -250,9 +228,7 @@ __global__ __launch_bounds__(256) void k_tpe_band_v(const V4<double>* __restrict
   for (int k = 0; k < NS; ++k) v[k] = red(v[k]);
   if (GRAD) v[13] = t.x * v[10] + t.y * v[11] + t.z * v[12];  // T.H: H holds multiples of T
   if (!valid || sub != 0) return;
-  double* out = part + I;
-#pragma unroll
-  for (int k = 0; k < NS; ++k) out[(size_t)k * nE] = v[k];
+  tpe_edge_record(v, GRAD, a.w, t.x, t.y, t.z, edge_out + 8 * (size_t)I, status);
 }
 
 // FP64 u_I (the vertex's incident edges in incidence order) and Lambda_v.
@@ -339,20 +315,20 @@ __global__ __launch_bounds__(kVpSumV* kVpSlots) void k_vp_sum(const float* __res
 // the vertex sums through e_I = g_i2 - g_i1: u_I = e_I / sqrt(l_I) enters
 // as a u of both endpoints, l_I as a term of both Lambdas, so
 //   dE/de_I = (I - T T^T / 2) (g_u(i1) + g_u(i2)) / sqrt(l_I) + (g_Lambda(i1) + g_Lambda(i2)) T.
-__global__ void k_vp_edge(const double* __restrict__ vout, const int2* __restrict__ edges,
-                          const int* __restrict__ inc_off, const int* __restrict__ inc,
-                          const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GT, int nE, int grad,
-                          double* __restrict__ edge_out) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nE) return;
+// Returns the edge's energy.
+__device__ __forceinline__ double vp_edge_one(const double* __restrict__ vout, const int2* __restrict__ edges,
+                                              const int* __restrict__ inc_off, const int* __restrict__ inc,
+                                              const V4<double>* __restrict__ GA, const V4<double>* __restrict__ GT,
+                                              int I, bool grad, double* __restrict__ edge_out) {
   const int2 e = edges[I];
   const int k1 = (inc[inc_off[e.x]] >> 1) == I ? 0 : 1;
   const int k2 = (inc[inc_off[e.y]] >> 1) == I ? 0 : 1;
   const double* o1 = vout + (size_t)kVpOut * e.x;
   const double* o2 = vout + (size_t)kVpOut * e.y;
   double* o = edge_out + 8 * (size_t)I;
-  o[0] += (k1 == 0 ? o1[0] : 0.0) + (k2 == 0 ? o2[0] : 0.0);
-  if (!grad) return;
+  const double E = o[0] + ((k1 == 0 ? o1[0] : 0.0) + (k2 == 0 ? o2[0] : 0.0));
+  o[0] = E;
+  if (!grad) return E;
   const V4<double> a = GA[I], t = GT[I];
   double gu[3];
   for (int k = 0; k < 3; ++k) gu[k] = o1[4 + 3 * k1 + k] + o2[4 + 3 * k2 + k];
@@ -365,6 +341,30 @@ __global__ void k_vp_edge(const double* __restrict__ vout, const int2* __restric
     o[1 + k] -= de[k];
     o[4 + k] += de[k];
   }
+  return E;
+}
+
+// vp_edge_one over the edges, a grid-stride loop; with partial set, also the
+// workgroup sums of the edge energies (the first pass of the fixed-order
+// total energy: partial[b] = sum of the energies of the edges b 256 + t +
+// k gridDim 256, by thread, then a tree over the 256 threads).
+__global__ __launch_bounds__(256) void k_vp_edge(const double* __restrict__ vout, const int2* __restrict__ edges,
+                                                 const int* __restrict__ inc_off, const int* __restrict__ inc,
+                                                 const V4<double>* __restrict__ GA,
+                                                 const V4<double>* __restrict__ GT, int nE, int grad,
+                                                 double* __restrict__ edge_out, double* __restrict__ partial) {
+  __shared__ double sm[256];
+  double acc = 0.0;
+  for (int I = blockIdx.x * 256 + threadIdx.x; I < nE; I += gridDim.x * 256)
+    acc += vp_edge_one(vout, edges, inc_off, inc, GA, GT, I, grad != 0, edge_out);
+  if (!partial) return;
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
 }
 
 // dE_v = the direct vertex gradient plus the endpoint partials of the edges at v.
@@ -388,12 +388,6 @@ __global__ void k_vp_gather(const double* __restrict__ vout, const double* __res
   if (!(isfinite(gx) & isfinite(gy) & isfinite(gz))) latch(status, kFlagResultNonfinite);
 }
 
-void launch_vertex_geometry(const Curve& c, const double* gamma, hipStream_t s) {
-  hipLaunchKernelGGL(k_vgeom, dim3(vp_cdiv(c.nV, 256)), dim3(256), 0, s, gamma, (const V4<double>*)c.gd.a,
-                     (const V4<double>*)c.gd.t, (const int*)c.inc_off, (const int*)c.inc, c.nV, c.vg[0], c.vg[1],
-                     c.vg[2]);
-}
-
 template <int EC, bool GRAD>
 static void run_vp(const Curve& c, double beta, hipStream_t s) {
   const bool timed = GRAD && c.timer && c.timer->on;
@@ -402,9 +396,10 @@ static void run_vp(const Curve& c, double beta, hipStream_t s) {
                      (const V4<float>*)c.vg[0], (const V4<float>*)c.vg[1], (const V4<float>*)c.vg[2],
                      (const int4*)c.vinfo, c.nV, c.vsrc_per_chunk, (float)(0.5 * beta), (float)beta, c.vpart);
   if (timed) c.timer->mark(c.timer->tpe, s);
-  hipLaunchKernelGGL((k_tpe_band_v<EC, GRAD>), dim3(vp_cdiv(c.nE, 256 / kBandLanes)), dim3(256), 0, s, (const V4<double>*)c.gd.a,
-                     (const V4<double>*)c.gd.t, (const int2*)c.edges, (const int4*)c.cinfo,
-                     (const int*)c.chain_edge, (const int4*)c.vinfo, c.nE, 0.5 * beta, beta, c.part);
+  hipLaunchKernelGGL((k_tpe_band_v<EC, GRAD>), dim3(vp_cdiv(c.nE, 256 / kBandLanes)), dim3(256), 0, s,
+                     (const V4<double>*)c.gd.a, (const V4<double>*)c.gd.t, (const int2*)c.edges,
+                     (const int4*)c.cinfo, (const int*)c.chain_edge, (const int4*)c.vinfo, c.nE, 0.5 * beta, beta,
+                     c.edge_out, c.status);
 }
 
 rc_status launch_tpe_vp_pairs(const Curve& c, double beta, bool grad, hipStream_t s) {
@@ -426,14 +421,15 @@ rc_status launch_tpe_vp_pairs(const Curve& c, double beta, bool grad, hipStream_
   return RC_OK;
 }
 
-rc_status launch_tpe_vp_finish(const Curve& c, double beta, bool grad, double* dE, hipStream_t s) {
+rc_status launch_tpe_vp_finish(const Curve& c, double beta, bool grad, double* dE, double* energy_partial,
+                               hipStream_t s) {
   const int NS = grad ? kVpSlots : 1;
   hipLaunchKernelGGL(k_vp_sum, dim3(vp_cdiv(c.nV, kVpSumV)), dim3(kVpSumV * NS), 0, s, (const float*)c.vpart,
                      c.vchunk, NS, c.nV, beta, (const V4<double>*)c.gd.a, (const V4<double>*)c.gd.t,
                      (const int*)c.inc_off, (const int*)c.inc, c.vout, c.status);
-  hipLaunchKernelGGL(k_vp_edge, dim3(vp_cdiv(c.nE, 256)), dim3(256), 0, s, (const double*)c.vout,
-                     (const int2*)c.edges, (const int*)c.inc_off, (const int*)c.inc, (const V4<double>*)c.gd.a,
-                     (const V4<double>*)c.gd.t, c.nE, grad ? 1 : 0, c.edge_out);
+  hipLaunchKernelGGL(k_vp_edge, dim3(c.red_blocks), dim3(256), 0, s, (const double*)c.vout, (const int2*)c.edges,
+                     (const int*)c.inc_off, (const int*)c.inc, (const V4<double>*)c.gd.a, (const V4<double>*)c.gd.t,
+                     c.nE, grad ? 1 : 0, c.edge_out, energy_partial);
   RC_TRY(launch_penalties(c, grad, s));
   if (grad && dE)
     hipLaunchKernelGGL(k_vp_gather, dim3(vp_cdiv(c.nV, 256)), dim3(256), 0, s, (const double*)c.vout,

@@ -479,4 +479,28 @@ __device__ __forceinline__ R sobolev_entry(int v, int w, const V4<double>* __res
   return acc;
 }
 
+// The record of edge I from its pair sums s (the kTpeSlots accumulators):
+// o = (E_I, dE/dg_i1 (3), dE/dg_i2 (3)).  A non-finite sum of an edge with a
+// finite length means that a disjoint pair's kernel overflowed: coincident
+// (or nearly coincident) vertices of disjoint edges, where the energy is
+// infinite (Sec. 4.1); it is latched.
+__device__ __forceinline__ void tpe_edge_record(const double (&s)[kTpeSlots], bool grad, double l, double Tx,
+                                                double Ty, double Tz, double* __restrict__ o,
+                                                unsigned* __restrict__ status) {
+  o[0] = l * s[0];
+  bool fin = isfinite(s[0]);
+  if (grad)
+    for (int k = 1; k < kTpeSlots; ++k) fin &= isfinite(s[k]);
+  if (!fin && isfinite(l) && l > 0.0) latch(status, kFlagPairOverflow);
+  if (!grad) return;
+  const double S = s[1];
+  const double Hx = s[10] - s[13] * Tx, Hy = s[11] - s[13] * Ty, Hz = s[12] - s[13] * Tz;
+  o[1] = -Tx * S + l * (s[2] - s[8] * Tx) + 2.0 * Hx;
+  o[2] = -Ty * S + l * (s[3] - s[8] * Ty) + 2.0 * Hy;
+  o[3] = -Tz * S + l * (s[4] - s[8] * Tz) + 2.0 * Hz;
+  o[4] = Tx * S + l * (s[5] - s[9] * Tx) - 2.0 * Hx;
+  o[5] = Ty * S + l * (s[6] - s[9] * Ty) - 2.0 * Hy;
+  o[6] = Tz * S + l * (s[7] - s[9] * Tz) - 2.0 * Hz;
+}
+
 }  // namespace rc

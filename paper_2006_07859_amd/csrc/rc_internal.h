@@ -263,7 +263,6 @@ rc_status launch_first_collision(const Curve& c, const double* gamma, const doub
 // The FP32 vertex-pair sums and the FP64 near band (part chunk 0), then,
 // after the band's edge finalize, the vertex finalize, the edge partials and
 // the gather into dE.
-void launch_vertex_geometry(const Curve& c, const double* gamma, hipStream_t s);
 rc_status launch_tpe_vp_pairs(const Curve& c, double beta, bool grad, hipStream_t s);
 // Adds the penalties (c.pen) to the per-edge energy / endpoint-derivative slots of edge_out.
 rc_status launch_penalties(const Curve& c, bool grad, hipStream_t s);
@@ -271,7 +270,8 @@ rc_status launch_penalties(const Curve& c, bool grad, hipStream_t s);
 // per-edge energy and endpoint derivatives added to c.edge_out
 rc_status build_surface_potential(SurfacePotential& sp, const double* P_h, int nP, const int* F_h, int nF);
 rc_status launch_surface_potential(const Curve& c, bool grad, hipStream_t s);
-rc_status launch_tpe_vp_finish(const Curve& c, double beta, bool grad, double* dE, hipStream_t s);
+rc_status launch_tpe_vp_finish(const Curve& c, double beta, bool grad, double* dE, double* energy_partial,
+                               hipStream_t s);
 // Shared tail of the edge-midpoint kernels: sums nparts chunks of the
 // 10-slot partials, writes energy and dE.
 rc_status finalize_midpoint(const Curve& c, int nparts, double* energy, double* dE, hipStream_t s);
