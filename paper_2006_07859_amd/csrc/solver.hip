@@ -1279,10 +1279,12 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
   double bb;
   RC_TRY(fetch(c, c->scal, &bb, 1));
   const double bn = std::sqrt(bb);
+  c->last_bnorm = bn;
   hipMemsetAsync(x, 0, sizeof(double) * n3, s);
   *iters_out = 0;
   *res_out = 0.0;
   if (!(bn > 0)) return RC_OK;
+  const double tol = c->pcg_ref > bn ? std::min(0.5, o.tol * c->pcg_ref / bn) : o.tol;
   vec_copy(c->tmp2, r, n3, s);
   int it = 0;
   double res = 1.0, res_sweep = 1.0;  // residual at the start of the current sweep
@@ -1332,11 +1334,11 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
         set_error("projected PCG: the residual kept growing");
         return RC_ERR_NOT_CONVERGED;
       }
-      if (res < std::max(o.tol, o.inner_tol * res_sweep) || (o.replace_every > 0 && since >= o.replace_every) ||
+      if (res < std::max(tol, o.inner_tol * res_sweep) || (o.replace_every > 0 && since >= o.replace_every) ||
           stalled) {
         // true residual r = P (b - Abar x) (FP64); restart the recurrence from it
         // a loose solve (tol >= 1e-4) checks with its own operator
-        if (o.tol >= 1e-4) RC_TRY(apply_op(x, c->tmp));
+        if (tol >= 1e-4) RC_TRY(apply_op(x, c->tmp));
         else RC_TRY(apply_A(c, c->curve, x, c->tmp, RC_F64));
         vec_copy(b, r, n3, s);
         vec_axpby(-1.0, c->tmp, 1.0, r, n3, s);
@@ -1348,7 +1350,7 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
         res_sweep = res;
         ++c->last_sweeps;
         if (trace_on()) fprintf(stderr, "[rc pcg] it %d TRUE-res %.3e\n", it, res);
-        if (res < o.tol) converged = true;
+        if (res < tol) converged = true;
         break;
       }
       RC_TRY(precondition(c, o.solver, r, z));
@@ -1725,21 +1727,33 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
     tau = (2.0 / 3.0) * std::min(out->tau_max, 1.5 * ls.tau0);
   }
   bool any_projected = false;  // some trial reached the constraint tolerance
+  // Sec. 4.4 leaves the accuracy of the approximate Newton iteration's saddle solves open: the first
+  // increment of a trial is solved to the relative tolerance, the later ones (whose right-hand sides
+  // shrink with the violation) to the same absolute accuracy, so that their sum is about as accurate as
+  // the first; C x = -Phi holds for each whatever the solve's accuracy
+  struct RefReset {
+    rc_ctx* c;
+    ~RefReset() { c->pcg_ref = 0.0; }
+  } ref_reset{c};
   for (int bt = 0; bt <= ls.max_backtracks; ++bt) {
     vec_trial(gamma, g, c->scal + 16, tau, c->trial, n3, s);
     bool ok = (k == 0);
     int it = 0;
+    c->pcg_ref = 0.0;
     for (; k > 0 && it <= ls.max_proj_iter; ++it) {
       cons_values(c, c->trial, c->phi);
       RC_TRY(fetch(c, c->phi, phi_h.data(), k));
       bool done = true;
+      double worst = 0.0;  // max |Phi_i| / tol_i
       for (int i = 0; i < k; ++i) {
         double tol = ls.proj_tol * lbar;
         if (K.bary && i < 3) tol *= Ltot;             // barycenter rows carry units of length^2
         else if (K.total && i == 3 * K.bary) tol *= Ltot / lbar;  // total length: relative to L
         else if (i >= K.ext_tg && i < K.ext_tg + 2 * K.ntg) tol = ls.proj_tol;  // tangent rows: dimensionless
         if (!std::isfinite(phi_h[i]) || std::fabs(phi_h[i]) > tol) done = false;
+        worst = std::max(worst, std::fabs(phi_h[i]) / tol);
       }
+      if (trace_on()) fprintf(stderr, "[rc ls] tau %.3e projection %d: max |Phi|/tol %.3e\n", tau, it, worst);
       if (done) {
         ok = true;
         break;
@@ -1757,7 +1771,9 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
           if (c->lowp_levels > 0) po.lowp_outer = 2;  // the finest 16-bit block, assembled at gamma
         }
       }
+      c->last_bnorm = 0.0;  // set by the PCG solvers only
       RC_TRY(projection_increment(c, c->phi, c->dx, po, &pit));
+      if (it == 0) c->pcg_ref = c->last_bnorm;
       out->proj_solve_iters += pit;
       vec_axpby(1.0, c->dx, 1.0, c->trial, n3, s);
     }
