@@ -584,7 +584,7 @@ rc_status rc_step(rc_ctx* c, double* gamma, const rc_solve_opts* so, const rc_ls
   rc_stats local{};
   rc_status st = RC_OK;
   hipEvent_t ev[4];
-  for (hipEvent_t& e : ev) RC_HIP(hipEventCreate(&e));
+  for (hipEvent_t& e : ev) RC_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));  // timing only
   int nev = 0;
   RC_HIP(hipEventRecord(ev[nev++], s));
   do {

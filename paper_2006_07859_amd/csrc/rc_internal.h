@@ -101,10 +101,12 @@ __device__ __forceinline__ void latch(unsigned* status, unsigned flag) {
 struct KernelTimer {
   bool on = false;
   std::vector<hipEvent_t> tpe, sob, lowp, asm32, sob64, basm, bh;  // start/stop pairs, in launch order
+  // timing-only events: no system-scope fence (no cache writeback and invalidation between the kernels
+  // they bracket); elapsed times are read after the stream has been synchronised
   void mark(std::vector<hipEvent_t>& v, hipStream_t s) {
     if (!on) return;
     hipEvent_t e;
-    hipEventCreate(&e);
+    hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     hipEventRecord(e, s);
     v.push_back(e);
   }
