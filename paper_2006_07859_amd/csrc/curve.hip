@@ -305,9 +305,14 @@ rc_status Curve::enable_vertex_pairs() {
   std::vector<int4> hv(nV);
   for (int v = 0; v < nV; ++v) hv[v] = make_int4(-1 - v, 0, 1, 0);  // isolated vertex: a chain of its own
   std::vector<Chain> chs = chains_of(*this);
+  std::vector<int> hc;  // the chains' vertices in order; a chain is named by its start in hc
+  hc.reserve(nV);
   for (size_t k = 0; k < chs.size(); ++k) {
-    const int m = (int)chs[k].verts.size();
-    for (int p = 0; p < m; ++p) hv[chs[k].verts[p]] = make_int4((int)k, p, m, chs[k].loop ? 1 : 0);
+    const int m = (int)chs[k].verts.size(), start = (int)hc.size();
+    for (int p = 0; p < m; ++p) {
+      hv[chs[k].verts[p]] = make_int4(start, p, m, chs[k].loop ? 1 : 0);
+      hc.push_back(chs[k].verts[p]);
+    }
   }
   // source chunks: about 4,096 workgroups (16 per compute unit); at 16,384 vertices one source tile
   // per chunk (measured on one MI355X: 0.384 ms per energy + differential launch against 0.416 ms
@@ -316,10 +321,14 @@ rc_status Curve::enable_vertex_pairs() {
   vchunk = std::max(1, std::min(tb, (4096 + tb - 1) / tb));
   vsrc_per_chunk = (nV + vchunk - 1) / vchunk;
   RC_TRY(dmalloc(&vinfo, nV));
+  RC_TRY(dmalloc(&vchain, std::max<size_t>(1, hc.size())));
   for (int k = 0; k < 3; ++k) RC_TRY(dmalloc(&vg[k], nV));
+  for (int k = 0; k < 3; ++k) RC_TRY(dmalloc(&vgd[k], nV));
   RC_TRY(dmalloc(&vpart, (size_t)vchunk * kVpSlots * nV));
+  RC_TRY(dmalloc(&vband, (size_t)kVpSlots * nV));
   RC_TRY(dmalloc(&vout, (size_t)kVpOut * nV));
   RC_HIP(hipMemcpy(vinfo, hv.data(), sizeof(int4) * nV, hipMemcpyHostToDevice));
+  if (!hc.empty()) RC_HIP(hipMemcpy(vchain, hc.data(), sizeof(int) * hc.size(), hipMemcpyHostToDevice));
   vp = true;
   return RC_OK;
 }
@@ -328,14 +337,17 @@ void Curve::release() {
   void* ptrs[] = {edges, inc_off, inc, gf.a, gf.b, gf.t, gd.a, gd.b, gd.t,
                   rhs_f[0], rhs_f[1], rhs_d[0], rhs_d[1], part, edge_out, red, cinfo, chain_edge,
                   inst_voff, inst_eoff, inst_of_edge, inst_of_vertex, items, nch_e, counter,
-                  vinfo, vg[0], vg[1], vg[2], vpart, vout};
+                  vinfo, vchain, vg[0], vg[1], vg[2], vgd[0], vgd[1], vgd[2], vpart, vband, vout};
   for (void* p : ptrs)
     if (p) hipFree(p);
   spot.release();
   vp = false;
   vinfo = nullptr;
+  vchain = nullptr;
   vg[0] = vg[1] = vg[2] = nullptr;
+  vgd[0] = vgd[1] = vgd[2] = nullptr;
   vpart = nullptr;
+  vband = nullptr;
   vout = nullptr;
   inst_voff = inst_eoff = inst_of_edge = inst_of_vertex = nch_e = counter = nullptr;
   items = nullptr;

@@ -36,10 +36,10 @@ ExpCase exp_case(double alpha, double beta) {
 // ---------------------------------------------------------------------------
 // a_I = (g_i1, l_I), b_I = (g_i2, 0), T_I = (e_I / l_I, 0) in FP64 and, when
 // Af is set, the same values rounded to FP32 (the FP32 pair kernels' copy).
-// When P is set (the vertex-pair form) thread v also writes the FP32 vertex
+// When P is set (the vertex-pair form) thread v also writes the vertex
 // geometry (g_v, Lambda_v), u_0, u_1 (sqrt(l_I) T_I of v's first two incident
-// edges in incidence order), its incident edges recomputed from gamma in the
-// same arithmetic.  A non-finite coordinate and a zero-length edge (l_I = 0:
+// edges in incidence order) in FP32 (P, U0, U1) and FP64 (Pd, U0d, U1d), its
+// incident edges recomputed from gamma in the same arithmetic.  A non-finite coordinate and a zero-length edge (l_I = 0:
 // T_I is undefined, Sec. 4 Notation) are latched.
 __device__ __forceinline__ double edge_vector(const double* __restrict__ gamma, int2 e, double (&p)[3],
                                               double (&q)[3], double (&d)[3]) {
@@ -57,7 +57,8 @@ __global__ void k_geometry(const double* __restrict__ gamma, const int2* __restr
                            V4<float>* __restrict__ Af, V4<float>* __restrict__ Bf, V4<float>* __restrict__ Tf,
                            const int* __restrict__ inc_off, const int* __restrict__ inc, int nV,
                            V4<float>* __restrict__ P, V4<float>* __restrict__ U0, V4<float>* __restrict__ U1,
-                           unsigned* __restrict__ status) {
+                           V4<double>* __restrict__ Pd, V4<double>* __restrict__ U0d,
+                           V4<double>* __restrict__ U1d, unsigned* __restrict__ status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nE) {
     double p[3], q[3], d[3];
@@ -88,9 +89,13 @@ __global__ void k_geometry(const double* __restrict__ gamma, const int2* __restr
 #pragma unroll
       for (int c = 0; c < 3; ++c) u[k - k0][c] = sl * (d[c] * il);
     }
-    P[i] = V4<float>{(float)gamma[3 * i], (float)gamma[3 * i + 1], (float)gamma[3 * i + 2], (float)lam};
+    const double x0 = gamma[3 * i], x1 = gamma[3 * i + 1], x2 = gamma[3 * i + 2];
+    P[i] = V4<float>{(float)x0, (float)x1, (float)x2, (float)lam};
     U0[i] = V4<float>{(float)u[0][0], (float)u[0][1], (float)u[0][2], 0.f};
     U1[i] = V4<float>{(float)u[1][0], (float)u[1][1], (float)u[1][2], 0.f};
+    Pd[i] = V4<double>{x0, x1, x2, lam};
+    U0d[i] = V4<double>{u[0][0], u[0][1], u[0][2], 0.0};
+    U1d[i] = V4<double>{u[1][0], u[1][1], u[1][2], 0.0};
   }
 }
 
@@ -940,7 +945,8 @@ rc_status launch_geometry(const Curve& c, const double* gamma, rc_dtype prec, hi
   const int n = vp ? std::max(c.nE, c.nV) : c.nE;
   hipLaunchKernelGGL(k_geometry, dim3(cdiv(n, 256)), dim3(256), 0, s, gamma, c.edges, c.nE, c.gd.a, c.gd.b, c.gd.t,
                      f32 ? c.gf.a : nullptr, f32 ? c.gf.b : nullptr, f32 ? c.gf.t : nullptr, c.inc_off, c.inc, c.nV,
-                     vp ? c.vg[0] : nullptr, vp ? c.vg[1] : nullptr, vp ? c.vg[2] : nullptr, c.status);
+                     vp ? c.vg[0] : nullptr, vp ? c.vg[1] : nullptr, vp ? c.vg[2] : nullptr,
+                     vp ? c.vgd[0] : nullptr, vp ? c.vgd[1] : nullptr, vp ? c.vgd[2] : nullptr, c.status);
   RC_HIP(hipGetLastError());
   return RC_OK;
 }

@@ -38,14 +38,22 @@ namespace rc {
 
 static inline int vp_cdiv(int a, int b) { return (a + b - 1) / b; }
 
-constexpr int kBandLanes = 16;  // lanes per target edge of the FP64 near band (a power of two, <= 64)
+// The FP64 near band (vertex pairs at most kBand steps apart along a chain,
+// which the FP32 kernel masks) in one launch of two parts: the pairs at
+// least kVpMinDist apart in the vertex-pair form (every edge at v is then
+// disjoint from every edge at w), kBandLanes lanes per target vertex; the
+// pairs closer than that in the edge-pair form with the exact shared-vertex
+// exclusion, kNearLanes lanes per target edge.
+constexpr int kVpMinDist = 3;
+constexpr int kBandLanes = 16;  // a power of two, <= 64
+constexpr int kNearLanes = 8;   // a power of two, >= 2 (kVpMinDist - 1) + 3 edges of the window
 
-// Same chain and at most kBand steps apart (cyclically on a loop).
-__device__ __forceinline__ bool vert_near(int4 a, int4 b) {
+// Same chain and at most K steps apart (cyclically on a loop).
+__device__ __forceinline__ bool vert_near(int4 a, int4 b, int K = kBand) {
   if (a.x != b.x) return false;
   int d = abs(b.y - a.y);
   if (a.w) d = min(d, a.z - d);
-  return d <= kBand;
+  return d <= K;
 }
 
 // All ordered vertex pairs (v, w) more than kBand steps apart: a thread owns
@@ -162,23 +170,20 @@ __global__ __launch_bounds__(kTile) void k_vp_pairs(const V4<float>* __restrict_
   }
 }
 
-// FP64 near band of the vertex-pair form: for target edge I, every edge J of
-// its chain at most kBand + 1 steps away, in the edge-pair form with the
-// exact shared-vertex exclusion, keeping only the vertex pairs at most kBand
-// steps apart (the ones the vertex-pair kernel masks).  kBandLanes lanes per
-// target edge (about 4 of its 2 kBand + 3 band edges each, so that 16 waves a
-// compute unit hide the FP64 latency), summed across the lanes by a fixed
-// butterfly; writes the edge's record to edge_out (tpe_edge_record), to which
-// the vertex sums are added later.
-template <int EC, bool GRAD>
-__global__ __launch_bounds__(256) void k_tpe_band_v(const V4<double>* __restrict__ GA,
-                                                    const V4<double>* __restrict__ GT, const int2* __restrict__ edges,
-                                                    const int4* __restrict__ cinfo, const int* __restrict__ chain_edge,
-                                                    const int4* __restrict__ vinfo, int nE, double half_beta,
-                                                    double beta, double* __restrict__ edge_out,
-                                                    unsigned* __restrict__ status) {
-  const int tg = blockIdx.x * blockDim.x + threadIdx.x;
-  const int I = tg / kBandLanes, sub = tg % kBandLanes;
+// Near band, edge-pair part: for target edge I, every edge J of its chain at
+// most KB + 1 steps away, in the edge-pair form with the exact shared-vertex
+// exclusion, keeping only the vertex pairs at most KB steps apart.  LANES
+// lanes per target edge (tg: the thread's index in this part), summed across
+// the lanes by a fixed butterfly; writes the edge's record to edge_out
+// (tpe_edge_record), to which the vertex sums are added later.
+template <int EC, bool GRAD, int KB, int LANES>
+__device__ __forceinline__ void near_edge_pairs(int tg, const V4<double>* __restrict__ GA,
+                                                const V4<double>* __restrict__ GT, const int2* __restrict__ edges,
+                                                const int4* __restrict__ cinfo, const int* __restrict__ chain_edge,
+                                                const int4* __restrict__ vinfo, int nE, double half_beta,
+                                                double beta, double* __restrict__ edge_out,
+                                                unsigned* __restrict__ status) {
+  const int I = tg / LANES, sub = tg % LANES;
   const bool valid = I < nE;
   double E = 0, S = 0, G1x = 0, G1y = 0, G1z = 0, G2x = 0, G2y = 0, G2z = 0;
   double Gt1 = 0, Gt2 = 0, Hx = 0, Hy = 0, Hz = 0;
@@ -190,7 +195,7 @@ __global__ __launch_bounds__(256) void k_tpe_band_v(const V4<double>* __restrict
     const int4 ci = cinfo[I];
     const int4 va = vinfo[ei.x], vb = vinfo[ei.y];
     const int m = ci.z;
-    constexpr int W = kBand + 1;
+    constexpr int W = KB + 1;
     int q0, q1;
     if (ci.w && m <= 2 * W + 1) {
       q0 = 0;
@@ -202,14 +207,14 @@ __global__ __launch_bounds__(256) void k_tpe_band_v(const V4<double>* __restrict
       q0 = max(0, ci.y - W);
       q1 = min(m - 1, ci.y + W);
     }
-    for (int q = q0 + sub; q <= q1; q += kBandLanes) {
+    for (int q = q0 + sub; q <= q1; q += LANES) {
       const int qq = ((q % m) + m) % m;
       const int J = chain_edge[ci.x + qq];
       const int2 ej = edges[J];
       const bool skip = (ei.x == ej.x) | (ei.x == ej.y) | (ei.y == ej.x) | (ei.y == ej.y);
       const int4 vc = vinfo[ej.x], ve = vinfo[ej.y];
-      const int m4 = (vert_near(va, vc) ? 1 : 0) | (vert_near(va, ve) ? 2 : 0) | (vert_near(vb, vc) ? 4 : 0) |
-                     (vert_near(vb, ve) ? 8 : 0);
+      const int m4 = (vert_near(va, vc, KB) ? 1 : 0) | (vert_near(va, ve, KB) ? 2 : 0) |
+                     (vert_near(vb, vc, KB) ? 4 : 0) | (vert_near(vb, ve, KB) ? 8 : 0);
       const V4<double> qa = GA[J], qt = GT[J];
       tpe_edge_pair<double, EC, GRAD, true, true>(a.x, a.y, a.z, t.x, t.y, t.z, a.w, qa.x, qa.y, qa.z, qt.x, qt.y,
                                                   qt.z, qa.w, skip ? 0.0 : 0.25 * qa.w, skip ? 1.0 : 0.0, 1.0,
@@ -219,7 +224,7 @@ __global__ __launch_bounds__(256) void k_tpe_band_v(const V4<double>* __restrict
   }
   auto red = [](double v) {  // butterfly over the group: the same sum, in the same order, on every lane
 #pragma unroll
-    for (int o = 1; o < kBandLanes; o <<= 1) v += __shfl_xor(v, o, 64);
+    for (int o = 1; o < LANES; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
   };
   constexpr int NS = GRAD ? kTpeSlots : 1;
@@ -229,6 +234,110 @@ __global__ __launch_bounds__(256) void k_tpe_band_v(const V4<double>* __restrict
   if (GRAD) v[13] = t.x * v[10] + t.y * v[11] + t.z * v[12];  // T.H: H holds multiples of T
   if (!valid || sub != 0) return;
   tpe_edge_record(v, GRAD, a.w, t.x, t.y, t.z, edge_out + 8 * (size_t)I, status);
+}
+
+// Near band, vertex-pair part: for target vertex v, the vertices w of its
+// chain with kVpMinDist <= distance <= kBand, in FP64 with the sums of
+// k_vp_pairs (the same slots and arithmetic).  kBandLanes lanes per target
+// vertex (tg: the thread's index in this part), summed across the lanes by
+// a fixed butterfly; written to vband[slot][v] (zeros for a vertex without
+// such pairs).
+template <int EC, bool GRAD>
+__device__ __forceinline__ void near_vertex_pairs(int tg, const V4<double>* __restrict__ P,
+                                                  const V4<double>* __restrict__ U0,
+                                                  const V4<double>* __restrict__ U1, const int4* __restrict__ vinfo,
+                                                  const int* __restrict__ vchain, int nV, double half_beta,
+                                                  double* __restrict__ vband) {
+  const int v = tg / kBandLanes, sub = tg % kBandLanes;
+  const bool valid = v < nV;
+  constexpr int NS = GRAD ? kVpSlots : 1;
+  double acc[kVpSlots];
+#pragma unroll
+  for (int k = 0; k < kVpSlots; ++k) acc[k] = 0.0;
+  if (valid) {
+    const int4 ci = vinfo[v];
+    const int m = ci.z, pos = ci.y;
+    int q0 = 0, n = 0;  // candidate positions q0 + j, j < n (mod m on a loop)
+    if (ci.x < 0) n = 0;  // isolated vertex
+    else if (ci.w && m <= 2 * kBand + 1) n = m;
+    else if (ci.w) {
+      q0 = pos - kBand;
+      n = 2 * kBand + 1;
+    } else {
+      q0 = max(0, pos - kBand);
+      n = min(m - 1, pos + kBand) - q0 + 1;
+    }
+    const V4<double> p = P[v], a0 = U0[v], a1 = U1[v];
+    const double Lv = p.w;
+    for (int j = sub; j < n; j += kBandLanes) {
+      int q = q0 + j;
+      if (ci.w) q = ((q % m) + m) % m;
+      int dist = abs(q - pos);
+      if (ci.w) dist = min(dist, m - dist);
+      if (dist < kVpMinDist || dist > kBand) continue;
+      const int w = vchain[ci.x + q];
+      const V4<double> qp = P[w], w0 = U0[w], w1 = U1[w];
+      const double dx = p.x - qp.x, dy = p.y - qp.y, dz = p.z - qp.z;
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      const double tav = fma(a0.x, dx, fma(a0.y, dy, a0.z * dz));
+      const double tbv = fma(a1.x, dx, fma(a1.y, dy, a1.z * dz));
+      const double qv = fma(-tav, tav, fma(-tbv, tbv, Lv * r2));
+      double ri, pb;
+      tpe_powers<EC, double>(r2, half_beta, ri, pb);
+      const double a = pb * qp.w;
+      acc[0] = fma(a, qv, acc[0]);
+      if constexpr (GRAD) {
+        const double taw = fma(w0.x, dx, fma(w0.y, dy, w0.z * dz));
+        const double tbw = fma(w1.x, dx, fma(w1.y, dy, w1.z * dz));
+        const double qw = fma(-taw, taw, fma(-tbw, tbw, qp.w * r2));
+        acc[1] = fma(a, dx, acc[1]);
+        acc[2] = fma(a, dy, acc[2]);
+        acc[3] = fma(a, dz, acc[3]);
+        const double b0 = pb * taw, b1 = pb * tbw;
+        acc[4] = fma(b0, w0.x, fma(b1, w1.x, acc[4]));
+        acc[5] = fma(b0, w0.y, fma(b1, w1.y, acc[5]));
+        acc[6] = fma(b0, w0.z, fma(b1, w1.z, acc[6]));
+        const double c = (pb * ri) * fma(qp.w, qv, Lv * qw);
+        acc[7] = fma(c, dx, acc[7]);
+        acc[8] = fma(c, dy, acc[8]);
+        acc[9] = fma(c, dz, acc[9]);
+        const double e0 = a * tav, e1 = a * tbv;
+        acc[10] = fma(e0, dx, acc[10]);
+        acc[11] = fma(e0, dy, acc[11]);
+        acc[12] = fma(e0, dz, acc[12]);
+        acc[13] = fma(e1, dx, acc[13]);
+        acc[14] = fma(e1, dy, acc[14]);
+        acc[15] = fma(e1, dz, acc[15]);
+        acc[16] = fma(pb, fma(qp.w, r2, qw), acc[16]);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k)
+#pragma unroll
+    for (int o = 1; o < kBandLanes; o <<= 1) acc[k] += __shfl_xor(acc[k], o, 64);
+  if (!valid || sub != 0) return;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) vband[(size_t)k * nV + v] = acc[k];
+}
+
+// The near band in one launch: workgroups [0, nbv) take the vertex-pair part,
+// the rest the edge-pair part.
+template <int EC, bool GRAD>
+__global__ __launch_bounds__(256) void k_vp_near(const V4<double>* __restrict__ P, const V4<double>* __restrict__ U0,
+                                                 const V4<double>* __restrict__ U1, const int* __restrict__ vchain,
+                                                 int nV, int nbv, const V4<double>* __restrict__ GA,
+                                                 const V4<double>* __restrict__ GT, const int2* __restrict__ edges,
+                                                 const int4* __restrict__ cinfo, const int* __restrict__ chain_edge,
+                                                 const int4* __restrict__ vinfo, int nE, double half_beta,
+                                                 double beta, double* __restrict__ vband,
+                                                 double* __restrict__ edge_out, unsigned* __restrict__ status) {
+  if ((int)blockIdx.x < nbv)  // uniform over the workgroup
+    near_vertex_pairs<EC, GRAD>(blockIdx.x * 256 + threadIdx.x, P, U0, U1, vinfo, vchain, nV, half_beta, vband);
+  else
+    near_edge_pairs<EC, GRAD, kVpMinDist - 1, kNearLanes>((blockIdx.x - nbv) * 256 + threadIdx.x, GA, GT, edges,
+                                                          cinfo, chain_edge, vinfo, nE, half_beta, beta, edge_out,
+                                                          status);
 }
 
 // FP64 u_I (the vertex's incident edges in incidence order) and Lambda_v.
@@ -250,13 +359,14 @@ __device__ __forceinline__ double vertex_u(const V4<double>* __restrict__ GA, co
   return lam;
 }
 
-// Per vertex: sums the chunks and writes
+// Per vertex: sums the chunks and the FP64 near band and writes
 // vout[v] = (E_v, direct gradient (3), dE/du_0 (3), dE/du_1 (3), dE/dLambda_v, 0).
 // A thread per (slot, vertex) adds the slot's chunk partials in chunk order in
 // FP64 (eight loads in flight; kVpSumV consecutive vertices make one 128-byte
 // line per slot and chunk), then one thread per vertex finishes from LDS.
 constexpr int kVpSumV = 32;
-__global__ __launch_bounds__(kVpSumV* kVpSlots) void k_vp_sum(const float* __restrict__ part, int nchunk, int NS,
+__global__ __launch_bounds__(kVpSumV* kVpSlots) void k_vp_sum(const float* __restrict__ part,
+                                                              const double* __restrict__ vband, int nchunk, int NS,
                                                               int nV, double beta, const V4<double>* __restrict__ GA,
                                                               const V4<double>* __restrict__ GT,
                                                               const int* __restrict__ inc_off,
@@ -278,7 +388,7 @@ __global__ __launch_bounds__(kVpSumV* kVpSlots) void k_vp_sum(const float* __res
       for (int u = 0; u < 8; ++u) a += (double)t[u];
     }
     for (; c < nchunk; ++c) a += (double)p[(size_t)c * stride];
-    sm[k][j] = a;
+    sm[k][j] = a + vband[(size_t)k * nV + v];  // then the FP64 near band
   }
   __syncthreads();
   if (k != 0 || v >= nV) return;
@@ -396,10 +506,12 @@ static void run_vp(const Curve& c, double beta, hipStream_t s) {
                      (const V4<float>*)c.vg[0], (const V4<float>*)c.vg[1], (const V4<float>*)c.vg[2],
                      (const int4*)c.vinfo, c.nV, c.vsrc_per_chunk, (float)(0.5 * beta), (float)beta, c.vpart);
   if (timed) c.timer->mark(c.timer->tpe, s);
-  hipLaunchKernelGGL((k_tpe_band_v<EC, GRAD>), dim3(vp_cdiv(c.nE, 256 / kBandLanes)), dim3(256), 0, s,
+  const int nbv = vp_cdiv(c.nV, 256 / kBandLanes), nbe = vp_cdiv(c.nE, 256 / kNearLanes);
+  hipLaunchKernelGGL((k_vp_near<EC, GRAD>), dim3(nbv + nbe), dim3(256), 0, s, (const V4<double>*)c.vgd[0],
+                     (const V4<double>*)c.vgd[1], (const V4<double>*)c.vgd[2], (const int*)c.vchain, c.nV, nbv,
                      (const V4<double>*)c.gd.a, (const V4<double>*)c.gd.t, (const int2*)c.edges,
                      (const int4*)c.cinfo, (const int*)c.chain_edge, (const int4*)c.vinfo, c.nE, 0.5 * beta, beta,
-                     c.edge_out, c.status);
+                     c.vband, c.edge_out, c.status);
 }
 
 rc_status launch_tpe_vp_pairs(const Curve& c, double beta, bool grad, hipStream_t s) {
@@ -425,7 +537,7 @@ rc_status launch_tpe_vp_finish(const Curve& c, double beta, bool grad, double* d
                                hipStream_t s) {
   const int NS = grad ? kVpSlots : 1;
   hipLaunchKernelGGL(k_vp_sum, dim3(vp_cdiv(c.nV, kVpSumV)), dim3(kVpSumV * NS), 0, s, (const float*)c.vpart,
-                     c.vchunk, NS, c.nV, beta, (const V4<double>*)c.gd.a, (const V4<double>*)c.gd.t,
+                     (const double*)c.vband, c.vchunk, NS, c.nV, beta, (const V4<double>*)c.gd.a, (const V4<double>*)c.gd.t,
                      (const int*)c.inc_off, (const int*)c.inc, c.vout, c.status);
   hipLaunchKernelGGL(k_vp_edge, dim3(c.red_blocks), dim3(256), 0, s, (const double*)c.vout, (const int2*)c.edges,
                      (const int*)c.inc_off, (const int*)c.inc, (const V4<double>*)c.gd.a, (const V4<double>*)c.gd.t,

@@ -182,14 +182,20 @@ struct Curve {
   int* chain_edge = nullptr;       // edges in chain order (cinfo.x + position -> edge)
 
   // Vertex-pair form of the alpha = 2 energy + differential (chain graphs,
-  // FP32; enable_vertex_pairs): per vertex (chain, position, vertex count, is
-  // loop), the FP32 vertex geometry (x_v, Lambda_v), u_0, u_1 (sqrt(l) T of
-  // the vertex's incident edges in incidence order), the FP32 chunk partial
-  // sums [vchunk][kVpSlots][nV] and the finalised per-vertex values [nV][kVpOut].
+  // FP32; enable_vertex_pairs): per vertex (chain start in vchain, position,
+  // vertex count, is loop; an isolated vertex v has chain -1 - v), the chains'
+  // vertices in order (vchain), the FP32 and FP64 vertex geometry (x_v,
+  // Lambda_v), u_0, u_1 (sqrt(l) T of the vertex's incident edges in
+  // incidence order), the FP32 chunk partial sums [vchunk][kVpSlots][nV], the
+  // FP64 near-band sums [kVpSlots][nV] and the finalised per-vertex values
+  // [nV][kVpOut].
   bool vp = false;
   int4* vinfo = nullptr;
+  int* vchain = nullptr;
   V4<float>* vg[3] = {nullptr, nullptr, nullptr};
+  V4<double>* vgd[3] = {nullptr, nullptr, nullptr};
   float* vpart = nullptr;
+  double* vband = nullptr;
   double* vout = nullptr;
   int vchunk = 1, vsrc_per_chunk = 0;
   rc_status enable_vertex_pairs();
