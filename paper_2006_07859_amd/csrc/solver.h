@@ -210,7 +210,7 @@ struct rc_ctx {
   int lowp_levels = 0, lowp_fmt = 0, lowp_band = 0, lowp_outer = 0;
   int last_sweeps = 0;  // FP64 true-residual evaluations of the last PCG solve
   // PCG's residual norms are relative to |P b|; with pcg_ref > |P b| the tolerance is relative to pcg_ref
-  // instead (an absolute target, capped at 0.5 relative); last_bnorm is the last solve's |P b|
+  // instead (an absolute target, capped at 0.02 relative); last_bnorm is the last solve's |P b|
   double pcg_ref = 0.0, last_bnorm = 0.0;
   rc::Batch batch;      // batch contexts only
   // learned / hand-weighted multilevel preconditioner

@@ -1258,6 +1258,11 @@ __global__ void k_pcg_p(const double* __restrict__ rz_new, const double* __restr
   p[i] = z[i] + (rz_new[0] / rz_old[0]) * p[i];
 }
 
+// With an absolute reference (rc_ctx::pcg_ref) the relative tolerance is capped at this: every solve
+// still removes most of its right-hand side's rough part, to which the tangent-point energy is most
+// sensitive at fine resolutions
+constexpr double kPcgRefMaxTol = 0.02;
+
 static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve_opts& o, int* iters_out,
                            double* res_out) {
   hipStream_t s = c->stream;
@@ -1284,7 +1289,7 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
   *iters_out = 0;
   *res_out = 0.0;
   if (!(bn > 0)) return RC_OK;
-  const double tol = c->pcg_ref > bn ? std::min(0.5, o.tol * c->pcg_ref / bn) : o.tol;
+  const double tol = c->pcg_ref > bn ? std::min(kPcgRefMaxTol, o.tol * c->pcg_ref / bn) : o.tol;
   vec_copy(c->tmp2, r, n3, s);
   int it = 0;
   double res = 1.0, res_sweep = 1.0;  // residual at the start of the current sweep
@@ -1729,8 +1734,9 @@ rc_status line_search(rc_ctx* c, double* gamma, double E0, const double* dE, con
   bool any_projected = false;  // some trial reached the constraint tolerance
   // Sec. 4.4 leaves the accuracy of the approximate Newton iteration's saddle solves open: the first
   // increment of a trial is solved to the relative tolerance, the later ones (whose right-hand sides
-  // shrink with the violation) to the same absolute accuracy, so that their sum is about as accurate as
-  // the first; C x = -Phi holds for each whatever the solve's accuracy
+  // shrink with the violation) to the same absolute accuracy but at least to kPcgRefMaxTol relative, so
+  // that their sum is about as accurate as the first; C x = -Phi holds for each whatever the solve's
+  // accuracy
   struct RefReset {
     rc_ctx* c;
     ~RefReset() { c->pcg_ref = 0.0; }
