@@ -169,7 +169,10 @@ typedef struct {
   int32_t max_proj_iter; /* projection iterations per trial step */
   double proj_tol;       /* relative projection tolerance (times mean edge length) */
   double proj_solve_tol; /* PCG tolerance of the projection increments: C x = -Phi holds exactly
-                            whatever it is; it only sets how close x is to the A-norm minimiser */
+                            whatever it is; it only sets how close x is to the A-norm minimiser.
+                            The first increment of a trial step is solved to this relative
+                            tolerance, each later one to the same absolute accuracy but at least to
+                            2 % relative (an inexact Newton iteration; PCG solvers only) */
   int32_t ccd;           /* 1 = start the search at 2/3 of the first collision time tau_max of the curve
                             moved along -g/|g| (Sec. 4.4; rc_first_collision_time), sought up to
                             1.5 tau0, so tau0 without a collision; 0 = start at tau0 */
