@@ -150,6 +150,47 @@ def test_vertex_pair_form_against_edge_pair_form_and_oracle(lib, beta):
     assert relnorm(out[True][1], out[False][1]) < 5e-5
 
 
+@pytest.mark.parametrize("beta", [4.5, 4.8])
+def test_vertex_pair_near_band_boundaries(lib, beta):
+    """The FP64 near band of the vertex-pair form at its branch boundaries: loops of 64 to 67 vertices
+    (a loop of at most 2 * 32 + 1 vertices is near in full, a longer one only within 32 steps, so
+    the candidate window wraps onto itself or not) and open paths of 30 to 36 vertices (the window
+    clamped at one end, at both, or at neither for the middle vertices), with pairs 3 to 32 steps
+    apart in the vertex-pair form and closer ones in the edge-pair form; against the oracle at the
+    FP32 tolerances and against the edge-pair form."""
+    from paper_2006_07859_amd import RC_F32
+
+    banner(f"energy+dE f32 vertex-pair near band boundaries, (2,{beta})")
+    parts, edges, off = [], [], 0
+    for k, m in enumerate((64, 65, 66, 67)):
+        g, e = gen.trefoil(m, seed=10 + k)
+        parts.append(0.4 * g + [3.0 * k, 0.0, 0.0])
+        edges.append(e + off)
+        off += m
+    for k, m in enumerate((30, 33, 34, 35, 36)):
+        t = np.linspace(0.0, 1.0, m)
+        parts.append(np.stack([0.3 * np.cos(4 * t) + 3.0 * k, 4.0 + 0.3 * np.sin(4 * t), 1.5 * t], 1))
+        edges.append(np.stack([np.arange(m - 1), np.arange(1, m)], 1) + off)
+        off += m
+    g = gen.round_to_f32(np.concatenate(parts))
+    e = np.concatenate(edges).astype(np.int32)
+    e = e[np.random.default_rng(4).permutation(len(e))]
+    E_ref, G_ref = tpe.differential(g, e, 2.0, beta)
+    out = {}
+    for vp in (True, False):
+        ctx = ctx_for(lib, g, e, 2.0, beta, RC_F32)
+        ctx.rc_use_vertex_pairs(vp)
+        E, dE = zeros(1), zeros(len(g), 3)
+        ctx.rc_differential(dev(g), E, dE)
+        assert host(E)[0] == pytest.approx(E_ref, rel=1e-5)
+        assert relnorm(host(dE), G_ref) < 1e-4
+        assert ctx.rc_sync_status() == (0, 0)
+        out[vp] = (host(E)[0], host(dE))
+        ctx.close()
+    assert out[True][0] == pytest.approx(out[False][0], rel=2e-6)
+    assert relnorm(out[True][1], out[False][1]) < 5e-5
+
+
 def test_triangle_has_zero_energy(lib):
     from paper_2006_07859_amd import RC_F64
 
