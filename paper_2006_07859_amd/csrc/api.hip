@@ -175,6 +175,8 @@ static rc_status create_ctx(int32_t nV, int32_t nE, const int32_t* edges_h, doub
   c->phi_cap = (size_t)nE + 4;
   RC_TRY(dalloc(&c->status_dev, 1));
   RC_HIP(hipMemsetAsync(c->status_dev, 0, sizeof(unsigned), c->stream));
+  RC_TRY(dalloc(&c->setup_flags, 1));
+  RC_HIP(hipMemsetAsync(c->setup_flags, 0, sizeof(unsigned), c->stream));
   c->curve.status = c->status_dev;
   RC_HIP(hipMemsetAsync(c->x, 0, sizeof(double) * n3, c->stream));
   RC_TRY(sync(c.get()));
@@ -218,6 +220,7 @@ rc_status rc_destroy(rc_ctx* c) {
   for (double* p : ps)
     if (p) hipFree(p);
   if (c->status_dev) hipFree(c->status_dev);
+  if (c->setup_flags) hipFree(c->setup_flags);
   delete c;
   return RC_OK;
 }
@@ -471,6 +474,7 @@ rc_status rc_project(rc_ctx* c, const double* gamma, const double* X, double* Y)
   RC_TRY(no_batch(c, "rc_project"));
   RC_TRY(check_ptrs({gamma, X, Y}));
   RC_TRY(cons_prepare(c, c->curve, c->cons, gamma));
+  RC_TRY(setup_check(c));
   cons_project(c, c->curve, c->cons, X, Y);
   RC_HIP(hipGetLastError());
   return RC_OK;

@@ -53,6 +53,17 @@ void cons_border_rows(const double* geo, const int* inc_off, const int* inc, con
 void free_weights(const double* w, const double* free, int nV, double* out, hipStream_t s);
 void mask_vertices(double* x, const double* w, const double* nrm, int nV, hipStream_t s);
 void unit_zero_diag(double* A, int n, hipStream_t s);
+// The border Schur complement's inverse on the device: S = D - K (nb x nb; K may be null), with a unit
+// diagonal where S has a zero one when unit_zero is set, inverted by Gauss-Jordan elimination with
+// partial pivoting into Sinv; a zero pivot sets `flag` in *flags (Sinv is then undefined).  nb <=
+// kSchurDevMax.
+constexpr int kSchurDevMax = 32;
+void schur_inverse_device(const double* D, const double* K, int nb, bool unit_zero, double* Sinv, unsigned* flags,
+                          unsigned flag, hipStream_t s);
+// *flags |= flag when *v != 0 (a factorisation's info word).
+void flag_if_nonzero(const int* v, unsigned* flags, unsigned flag, hipStream_t s);
+// y = x / sqrt(*sq), n entries (sq on the device).
+void vec_scale_rsqrt(const double* x, const double* sq, double* y, int n, hipStream_t s);
 void cons_path_coeffs(const double* geo, const int2* edges, const int* path_edge, const int* path_prev, int np,
                       const double* w, const double* nrm, double* ta, double* td, double* tc, hipStream_t s);
 void cons_scale_rows(const double* rows, const double* w, const double* nrm, int nV, int nrows, double* out,

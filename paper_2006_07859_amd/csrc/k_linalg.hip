@@ -838,6 +838,94 @@ void cons_sub_Zy(const double* Z, const double* yb, int nb, int np, double* yp, 
 }
 
 // ---------------------------------------------------------------------------
+// small device-side pieces of the constraint set-up (no host round trip)
+// ---------------------------------------------------------------------------
+// One workgroup; the matrix and its inverse in LDS.  The steps are those of
+// the host routine they replace: per column the first row of largest
+// magnitude as pivot, row swap, pivot row scaled by 1 / pivot, every other
+// row eliminated (multipliers read before the column is overwritten).
+__global__ __launch_bounds__(256) void k_schur_inverse(const double* __restrict__ D, const double* __restrict__ K,
+                                                       int n, int unit_zero, double* __restrict__ Sinv,
+                                                       unsigned* __restrict__ flags, unsigned flag) {
+  __shared__ double A[kSchurDevMax * kSchurDevMax], I[kSchurDevMax * kSchurDevMax], f[kSchurDevMax];
+  __shared__ int piv_s, bad_s;
+  const int t = threadIdx.x, nn = n * n;
+  for (int i = t; i < nn; i += 256) {
+    A[i] = D[i] - (K ? K[i] : 0.0);
+    I[i] = (i / n == i % n) ? 1.0 : 0.0;
+  }
+  if (t == 0) bad_s = 0;
+  __syncthreads();
+  if (unit_zero && t < n && A[t * n + t] == 0.0) A[t * n + t] = 1.0;
+  __syncthreads();
+  for (int col = 0; col < n; ++col) {
+    if (t == 0) {
+      int piv = col;
+      for (int r = col + 1; r < n; ++r)
+        if (fabs(A[r * n + col]) > fabs(A[piv * n + col])) piv = r;
+      piv_s = piv;
+      if (!(fabs(A[piv * n + col]) > 0.0)) bad_s = 1;
+    }
+    __syncthreads();
+    if (bad_s) break;  // uniform over the workgroup
+    const int piv = piv_s;
+    if (piv != col)
+      for (int j = t; j < n; j += 256) {
+        const double a = A[col * n + j], i = I[col * n + j];
+        A[col * n + j] = A[piv * n + j];
+        I[col * n + j] = I[piv * n + j];
+        A[piv * n + j] = a;
+        I[piv * n + j] = i;
+      }
+    __syncthreads();
+    const double d = 1.0 / A[col * n + col];
+    __syncthreads();  // every thread has read the pivot before its row is scaled
+    for (int j = t; j < n; j += 256) {
+      A[col * n + j] *= d;
+      I[col * n + j] *= d;
+    }
+    for (int r = t; r < n; r += 256) f[r] = r == col ? 0.0 : A[r * n + col];
+    __syncthreads();
+    for (int i = t; i < nn; i += 256) {
+      const double fr = f[i / n];
+      if (fr == 0.0) continue;
+      const int j = i % n;
+      A[i] -= fr * A[col * n + j];
+      I[i] -= fr * I[col * n + j];
+    }
+    __syncthreads();
+  }
+  if (bad_s) {
+    if (t == 0) atomicOr(flags, flag);
+    return;
+  }
+  for (int i = t; i < nn; i += 256) Sinv[i] = I[i];
+}
+
+void schur_inverse_device(const double* D, const double* K, int nb, bool unit_zero, double* Sinv, unsigned* flags,
+                          unsigned flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_schur_inverse, dim3(1), dim3(256), 0, s, D, K, nb, unit_zero ? 1 : 0, Sinv, flags, flag);
+}
+
+__global__ void k_flag_if_nonzero(const int* __restrict__ v, unsigned* __restrict__ flags, unsigned flag) {
+  if (threadIdx.x == 0 && *v != 0) atomicOr(flags, flag);
+}
+
+void flag_if_nonzero(const int* v, unsigned* flags, unsigned flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_flag_if_nonzero, dim3(1), dim3(64), 0, s, v, flags, flag);
+}
+
+__global__ void k_scale_rsqrt(const double* __restrict__ x, const double* __restrict__ sq, double* __restrict__ y,
+                              int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (1.0 / sqrt(sq[0])) * x[i];
+}
+
+void vec_scale_rsqrt(const double* x, const double* sq, double* y, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_rsqrt, dim3(cdiv(n, 256)), dim3(256), 0, s, x, sq, y, n);
+}
+
+// ---------------------------------------------------------------------------
 // the projector P x = x - C^T (C C^T)^-1 C x in three launches (nb <= 8)
 // ---------------------------------------------------------------------------
 // With K = C C^T split into the path block Kpp (tridiagonal), the border

@@ -17,6 +17,7 @@ namespace rc {
 // error plumbing
 // ---------------------------------------------------------------------------
 void set_error(const std::string& msg);
+const char* last_error();
 
 #define RC_HIP(call)                                                          \
   do {                                                                        \

@@ -203,6 +203,7 @@ struct rc_ctx {
   int bct_min_v = 0;
   rc::KernelTimer timer;
   unsigned* status_dev = nullptr;  // device status word (RC_FLAG_* bits latched by kernels)
+  unsigned* setup_flags = nullptr;  // device word: kSetup* bits latched by the constraint set-up (setup_check)
   unsigned status_host = 0;        // RC_FLAG_* bits latched by the host-side solver
   // precision path: the finest level's assembled 16-bit operator; levels
   // 0 .. lowp_levels-1 use their assembled operator in the current solve
@@ -243,7 +244,14 @@ bool trace_on();
 rc_status cons_alloc(rc_ctx* c, const Curve& cv, Cons& k, uint32_t mask, const std::vector<int>& pts = {},
                      const SurfSpec* surf = nullptr, const TangentSpec* tang = nullptr);
 void cons_free(Cons& k);
+// Failures of the constraint set-up latched in rc_ctx::setup_flags.
+constexpr unsigned kSetupGram = 1u;   // the path block's tridiagonal factorisation broke down
+constexpr unsigned kSetupSchur = 2u;  // the border Schur complement is singular
+// Enqueues the factors of C C^T (or C W C^T) without waiting for the device: a failed factorisation is
+// latched in c->setup_flags and reported by setup_check.
 rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma, const double* w = nullptr);
+// Waits for the stream, reports (and clears) the constraint set-up's latched failures.
+rc_status setup_check(rc_ctx* c);
 // With pop, the last launch also writes the operand of pop's next product,
 // taken of out (of xacc when pfrom_x); returns whether it did.
 bool cons_project(rc_ctx* c, const Curve& cv, Cons& k, const double* in, double* out, double* xacc = nullptr,

@@ -271,6 +271,11 @@ __global__ void k_negate(const double* __restrict__ in, double* __restrict__ out
   if (i < n) out[i] = -in[i];
 }
 
+__global__ void k_fill_u32(unsigned* __restrict__ x, int n, unsigned v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
 __global__ void k_fill(double* __restrict__ x, int n, double v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
@@ -499,13 +504,7 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma,
   if (np > 0) {
     cons_path_coeffs(k.geo, cv.edges, k.path_edge, k.path_prev, np, w, k.nrm, k.ta, k.td, k.tc, s);
     tri_prepare(k.ta, k.td, k.tc, k.tri, lo, uinv, k.sp_VW, k.sp_Rt, k.sp_tmp, tinfo, s);
-    int info = 0;
-    RC_HIP(hipMemcpyAsync(&info, tinfo, sizeof(int), hipMemcpyDeviceToHost, s));
-    RC_TRY(sync(c));
-    if (info != 0) {
-      set_error("edge-length constraint Gram matrix is not positive definite");
-      return RC_ERR_SINGULAR;
-    }
+    flag_if_nonzero(tinfo, c->setup_flags, kSetupGram, s);
   }
   if (k.prow)
     cons_project_pack(k.geo, cv.edges, k.path_edge, np, cv.inc_off, cv.inc, k.edge_path_row, nV, k.prow, k.pvert, s);
@@ -523,12 +522,16 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma,
       tri_solve(path_sys(k), k.Kpb, np, k.Z, np, nb, k.sp_g, k.sp_U, s);
       for (int r = 0; r < nb; ++r) vec_dots(k.Kpb, np, k.Z + (size_t)r * np, 0, np, nb, c->red, k.small + r * nb, s);
     }
+    // a border row that vanishes on the free vertices (a cut edge with both ends pinned) is zero
+    // in S: a unit diagonal gives it a zero multiplier
+    if (nb <= kSchurDevMax) {
+      schur_inverse_device(k.dots, np > 0 ? k.small : nullptr, nb, k.elim, k.Sinv, c->setup_flags, kSetupSchur, s);
+      return RC_OK;
+    }
     std::vector<double> S(nb * nb), kz(nb * nb, 0.0);
     RC_TRY(fetch(c, k.dots, S.data(), nb * nb));
     if (np > 0) RC_TRY(fetch(c, k.small, kz.data(), nb * nb));
     for (int i = 0; i < nb * nb; ++i) S[i] -= kz[i];
-    // a border row that vanishes on the free vertices (a cut edge with both ends pinned) is zero
-    // in S: a unit diagonal gives it a zero multiplier
     if (k.elim)
       for (int i = 0; i < nb; ++i)
         if (S[i * nb + i] == 0.0) S[i * nb + i] = 1.0;
@@ -537,8 +540,25 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma,
       return RC_ERR_SINGULAR;
     }
     RC_HIP(hipMemcpyAsync(k.Sinv, S.data(), sizeof(double) * nb * nb, hipMemcpyHostToDevice, s));
+    return sync(c);  // S is read by the copy
   }
-  return sync(c);
+  return RC_OK;
+}
+
+rc_status setup_check(rc_ctx* c) {
+  unsigned f = 0;
+  RC_HIP(hipMemcpyAsync(&f, c->setup_flags, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, c->stream, c->setup_flags, 1, 0u);
+  RC_TRY(sync(c));
+  if (f & kSetupGram) {
+    set_error("edge-length constraint Gram matrix is not positive definite");
+    return RC_ERR_SINGULAR;
+  }
+  if (f & kSetupSchur) {
+    set_error("constraint Schur complement is singular (dependent constraints?)");
+    return RC_ERR_SINGULAR;
+  }
+  return RC_OK;
 }
 
 // (wp, wb) -> (yp, yb) = (C C^T)^-1 w
@@ -996,6 +1016,10 @@ static rc_status apply_level(rc_ctx* c, int l, const double* X, double* Y) {
 // Learned smoother diagonals: the network's ratio prediction times this margin.
 constexpr double kLearnedMargin = 1.05;
 
+// scal[kPwSlot0 ..] holds the power iterations' squared norms, two per level (the context's scalar
+// buffer has 128 slots; the solvers use the first 20)
+constexpr int kPwSlot0 = 64, kPwSlots = 64;
+
 static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
   RC_TRY(mg_build(c));
   hipStream_t s = c->stream;
@@ -1011,7 +1035,6 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
     Curve& cv = const_cast<Curve&>(level_curve(c, l));
     const double* gl = l == 0 ? gamma : c->levels[l]->gamma;
     RC_TRY(launch_geometry(cv, gl, RC_F32, s));
-    if (l > 0) RC_TRY(cons_prepare(c, cv, level_cons(c, l), gl));
     // hierarchical operator: a block cluster tree of the level at its curve (not on the
     // coarsest level, whose dense saddle is assembled exactly)
     cv.hbvh = nullptr;
@@ -1051,6 +1074,11 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
       RC_TRY(launch_learned_diag(c->learn_Y + c->learn_off[l], level_curve(c, l).nV, kLearnedMargin, c->mg[l].diag,
                                  s));
   }
+  // every level's constraint factors: many small launches, enqueued while the device runs the
+  // operators' assembly above (none of them waits for the device)
+  for (int l = 0; l < nl; ++l)
+    RC_TRY(cons_prepare(c, level_curve(c, l), level_cons(c, l), l == 0 ? gamma : c->levels[l]->gamma));
+  std::vector<int> pw_levels;  // the levels whose smoother interval comes from power iteration
   for (int l = 0; l < nl - 1; ++l) {
     const Curve& cv = level_curve(c, l);
     Cons& K = level_cons(c, l);
@@ -1071,37 +1099,71 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
       continue;
     }
     if (c->mg_cg) continue;  // the CG smoother needs no spectral interval
-    // lambda_max of the smoother's preconditioned operator (P D^-1 P A P, or M A with the
-    // weighted projector M) by power iteration, warm-started from the last call's vector: at
-    // most 12 iterations, stopping once the estimate moves by less than 1 % after at least 3
-    // (warm start) or 8 (first call) of them
-    const int min_it = st.lmax > 0.0 ? 3 : 8;
-    double nrm = 0.0, prev = 0.0;
-    for (int it = 0; it < 12; ++it) {
-      if (c->mg_weighted) {
-        RC_TRY(apply_level(c, l, st.pw, st.t));
-        cons_project_w(c, cv, level_cons_w(c, l), st.w, st.t, st.d, 1.0, 0.0, nullptr);
-      } else {
-        cons_project(c, cv, K, st.pw, st.pw);
-        RC_TRY(apply_level(c, l, st.pw, st.t));
-        cons_project(c, cv, K, st.t, st.t);
-        vec_scale_diag_inv(st.t, st.diag, st.d, n, s);
-        cons_project(c, cv, K, st.d, st.d);
-      }
-      vec_dot(st.d, st.d, 3 * n, c->red, c->scal, s);
-      double h;
-      RC_TRY(fetch(c, c->scal, &h, 1));
-      nrm = std::sqrt(h);
+    pw_levels.push_back(l);
+  }
+  // lambda_max of the smoother's preconditioned operator (P D^-1 P A P, or M A with the weighted
+  // projector M) by power iteration, warm-started from the last call's vector: at most 12
+  // iterations, stopping once the estimate moves by less than 1 % after at least 3 (warm start) or 8
+  // (first call) of them.  The iterate is normalised on the device, and the levels' estimates of
+  // their last two iterations are read together once per round (a level's first round runs its
+  // minimum count).
+  const int npw = (int)pw_levels.size();
+  if (2 * npw > kPwSlots) {
+    set_error("multigrid setup: too many levels");
+    return RC_ERR_UNSUPPORTED;
+  }
+  auto power_step = [&](int q, int it) -> rc_status {  // one iteration on level pw_levels[q]
+    const int l = pw_levels[q];
+    const Curve& cv = level_curve(c, l);
+    Cons& K = level_cons(c, l);
+    MGLevelState& st = c->mg[l];
+    const int n = cv.nV;
+    if (c->mg_weighted) {
+      RC_TRY(apply_level(c, l, st.pw, st.t));
+      cons_project_w(c, cv, level_cons_w(c, l), st.w, st.t, st.d, 1.0, 0.0, nullptr);
+    } else {
+      cons_project(c, cv, K, st.pw, st.pw);
+      RC_TRY(apply_level(c, l, st.pw, st.t));
+      cons_project(c, cv, K, st.t, st.t);
+      vec_scale_diag_inv(st.t, st.diag, st.d, n, s);
+      cons_project(c, cv, K, st.d, st.d);
+    }
+    double* sq = c->scal + kPwSlot0 + 2 * q + (it & 1);
+    vec_dot(st.d, st.d, 3 * n, c->red, sq, s);
+    vec_scale_rsqrt(st.d, sq, st.pw, 3 * n, s);
+    return RC_OK;
+  };
+  std::vector<int> its(npw, 0);
+  std::vector<char> done(npw, 0);
+  std::vector<double> h(2 * std::max(npw, 1));
+  for (int round = 0; npw > 0; ++round) {
+    for (int q = 0; q < npw; ++q) {
+      if (done[q]) continue;
+      const int todo = round == 0 ? (c->mg[pw_levels[q]].lmax > 0.0 ? 3 : 8) : 1;
+      for (int k = 0; k < todo; ++k) RC_TRY(power_step(q, its[q]++));
+    }
+    RC_TRY(fetch(c, c->scal + kPwSlot0, h.data(), 2 * npw));
+    bool all = true;
+    for (int q = 0; q < npw; ++q) {
+      if (done[q]) continue;
+      const int it = its[q] - 1;  // the last iteration
+      const double nrm = std::sqrt(h[2 * q + (it & 1)]), prev = std::sqrt(h[2 * q + ((it + 1) & 1)]);
       if (!(nrm > 0)) {
         set_error("multigrid setup: zero operator");
         return RC_ERR_SINGULAR;
       }
-      vec_axpby(1.0 / nrm, st.d, 0.0, st.pw, 3 * n, s);
-      if (it + 1 >= min_it && std::fabs(nrm - prev) < 0.01 * nrm) break;
-      prev = nrm;
+      if (std::fabs(nrm - prev) < 0.01 * nrm || its[q] >= 12) {
+        done[q] = 1;
+        MGLevelState& st = c->mg[pw_levels[q]];
+        st.lmax = 1.1 * nrm;
+        if (trace_on())
+          fprintf(stderr, "[rc mg] level %d n %d lmax %.6e (%d iterations)\n", pw_levels[q],
+                  level_curve(c, pw_levels[q]).nV, nrm, its[q]);
+      } else {
+        all = false;
+      }
     }
-    st.lmax = 1.1 * nrm;
-    if (trace_on()) fprintf(stderr, "[rc mg] level %d n %d lmax %.6e\n", l, n, nrm);
+    if (all) break;
   }
   RC_TRY(dense_prepare(c, level_curve(c, nl - 1), level_cons(c, nl - 1), c->coarse,
                        nl == 1 ? gamma : c->levels[nl - 1]->gamma));
@@ -1378,7 +1440,7 @@ static rc_status pcg_solve(rc_ctx* c, const double* b, double* x, const rc_solve
 // ---------------------------------------------------------------------------
 // entry points used by the C ABI
 // ---------------------------------------------------------------------------
-rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o) {
+static rc_status prepare_solver_body(rc_ctx* c, const double* gamma, const rc_solve_opts& o) {
   if (o.solver < RC_SOLVE_DENSE || o.solver > RC_SOLVE_MG_FMG || o.solver == 3) {
     set_error("solve options: unknown solver kind");
     return RC_ERR_ARG;
@@ -1409,7 +1471,9 @@ rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o)
       L->curve.hbct = nullptr;
     }
   RC_TRY(load_geometry(c, gamma));
-  RC_TRY(cons_prepare(c, c->curve, c->cons, gamma));
+  const bool multigrid =
+      o.solver == RC_SOLVE_PCG_MG || o.solver == RC_SOLVE_PCG_LEARNED || o.solver == RC_SOLVE_MG_FMG;
+  if (!multigrid) RC_TRY(cons_prepare(c, c->curve, c->cons, gamma));  // (the multigrid set-up does every level)
   if (o.solver == RC_SOLVE_DENSE) return dense_prepare(c, c->curve, c->cons, c->dense, gamma);
   c->lowp_fmt = o.lowp;
   c->lowp_band = o.lowp_band;
@@ -1455,6 +1519,21 @@ rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o)
     return RC_OK;
   }
   return launch_sobolev(c->curve, c->alpha, c->beta, c->dtype, c->x, c->tmp, c->diag, c->stream);
+}
+
+// The solver's set-up, then one wait for the device: a constraint factorisation that failed anywhere in
+// the hierarchy is reported here (before any error it caused downstream).
+rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o) {
+  const rc_status st = prepare_solver_body(c, gamma, o);
+  const std::string msg = last_error();
+  const rc_status sc = setup_check(c);
+  if (st == RC_ERR_ARG || st == RC_ERR_UNSUPPORTED) {  // an option or size the set-up rejected
+    set_error(msg);
+    return st;
+  }
+  if (sc != RC_OK) return sc;
+  if (st != RC_OK) set_error(msg);
+  return st;
 }
 
 // Prepare and solve; the multilevel preconditioners fall back to multigrid
