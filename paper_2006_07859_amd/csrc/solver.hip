@@ -996,6 +996,19 @@ static rc_status mg_build(rc_ctx* c) {
   return RC_OK;
 }
 
+// After a failed set-up: the power iterations start cold again from their initial vectors (a set-up at
+// a non-finite curve leaves non-finite iterates behind, which would seed the next call's warm start).
+static void mg_reset_power(rc_ctx* c) {
+  if (!c->mg_built) return;
+  for (size_t l = 0; l < c->mg.size(); ++l) {
+    MGLevelState& st = c->mg[l];
+    const int n = level_curve(c, (int)l).nV;
+    hipLaunchKernelGGL(k_fill_pattern, dim3(cdiv(3 * n, 256)), dim3(256), 0, c->stream, st.pw, 3 * n,
+                       12345u + (unsigned)l);
+    st.lmax = 0.0;
+  }
+}
+
 // A X on a level: the block-cluster-tree product when the level has a tree
 // (FP64 sums whatever prec), else the matrix-free operator in precision prec.
 static rc_status apply_A(rc_ctx* c, const Curve& cv, const double* X, double* Y, rc_dtype prec) {
@@ -1527,6 +1540,7 @@ rc_status prepare_solver(rc_ctx* c, const double* gamma, const rc_solve_opts& o)
   const rc_status st = prepare_solver_body(c, gamma, o);
   const std::string msg = last_error();
   const rc_status sc = setup_check(c);
+  if (st != RC_OK || sc != RC_OK) mg_reset_power(c);
   if (st == RC_ERR_ARG || st == RC_ERR_UNSUPPORTED) {  // an option or size the set-up rejected
     set_error(msg);
     return st;

@@ -123,3 +123,40 @@ def test_solver_conditions_latch(lib):
     s, f = ctx.rc_sync_status()
     assert s == LINESEARCH and f == F.RC_FLAG_LINESEARCH, (s, f)
     ctx.close()
+
+
+def test_constraint_setup_failure_reported(lib):
+    """A constraint factorisation that breaks down is latched on the device during the set-up and
+    reported by the call that prepared it: a non-finite vertex makes a pivot of the edge-length rows'
+    tridiagonal block NaN, so rc_project and the multigrid gradient (whose set-up enqueues every
+    level's factors without waiting) return RC_ERR_SINGULAR; the next call at a valid curve succeeds
+    (the latch is cleared)."""
+    from paper_2006_07859_amd import (RC_C_BARYCENTER, RC_C_EDGE_LENGTH, RC_F32, RC_SOLVE_PCG_MG, Context,
+                                      default_solve_opts)
+    from paper_2006_07859_amd._lib import RcError
+
+    SINGULAR = 8
+    g, e, _ = gen.fourier_knot(1024, seed=1)
+    g = gen.round_to_f32(g)
+    n = len(g)
+    bad = g.copy()
+    bad[100] = np.nan
+    banner("constraint set-up failure: rc_project and multigrid gradient at a non-finite vertex")
+    ctx = Context(n, e, 2.0, 4.5, RC_F32)
+    ctx.rc_set_constraints(RC_C_BARYCENTER | RC_C_EDGE_LENGTH, dev(g))
+    X, Y = dev(np.random.default_rng(0).normal(size=(n, 3))), zeros(n, 3)
+    with pytest.raises(RcError) as ei:
+        ctx.rc_project(dev(bad), X, Y)
+    assert ei.value.status == SINGULAR
+    ctx.rc_project(dev(g), X, Y)
+    assert np.isfinite(Y.cpu().numpy()).all()
+    E, dE, gt = zeros(1), zeros(n, 3), zeros(n, 3)
+    ctx.rc_differential(dev(g), E, dE)
+    so = default_solve_opts(solver=RC_SOLVE_PCG_MG, tol=1e-6, mg_min_vertices=256)
+    with pytest.raises(RcError) as ei:
+        ctx.rc_sobolev_gradient(dev(bad), dE, gt, so)
+    assert ei.value.status == SINGULAR
+    st = ctx.rc_sobolev_gradient(dev(g), dE, gt, so)
+    assert st["residual"] < 1e-6
+    ctx.rc_sync_status()  # clears the non-finite input flag latched by the failed calls
+    ctx.close()
