@@ -1118,7 +1118,7 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
   // projector M) by power iteration, warm-started from the last call's vector: at most 12
   // iterations, stopping once the estimate moves by less than 1 % after at least 3 (warm start) or 8
   // (first call) of them.  The iterate is normalised on the device, and the levels' estimates of
-  // their last two iterations are read together once per round (a level's first round runs its
+  // their last two iterations are read together once per pass (a level's first pass runs its
   // minimum count).
   const int npw = (int)pw_levels.size();
   if (2 * npw > kPwSlots) {
@@ -1149,10 +1149,10 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
   std::vector<int> its(npw, 0);
   std::vector<char> done(npw, 0);
   std::vector<double> h(2 * std::max(npw, 1));
-  for (int round = 0; npw > 0; ++round) {
+  for (int pass = 0; npw > 0; ++pass) {
     for (int q = 0; q < npw; ++q) {
       if (done[q]) continue;
-      const int todo = round == 0 ? (c->mg[pw_levels[q]].lmax > 0.0 ? 3 : 8) : 1;
+      const int todo = pass == 0 ? (c->mg[pw_levels[q]].lmax > 0.0 ? 3 : 8) : 1;
       for (int k = 0; k < todo; ++k) RC_TRY(power_step(q, its[q]++));
     }
     RC_TRY(fetch(c, c->scal + kPwSlot0, h.data(), 2 * npw));
