@@ -170,7 +170,7 @@ static rc_status create_ctx(int32_t nV, int32_t nE, const int32_t* edges_h, doub
   for (double** v : vecs) RC_TRY(dalloc(v, n3));
   RC_TRY(dalloc(&c->diag, nV));
   RC_TRY(dalloc(&c->scal, 128));
-  RC_TRY(dalloc(&c->red, (size_t)dot_scratch_size(128)));
+  RC_TRY(dalloc(&c->red, (size_t)dot_scratch_size(kRedSets)));
   RC_TRY(dalloc(&c->phi, 2 * ((size_t)nE + 4)));
   c->phi_cap = (size_t)nE + 4;
   RC_TRY(dalloc(&c->status_dev, 1));

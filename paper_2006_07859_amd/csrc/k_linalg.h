@@ -8,7 +8,12 @@ namespace rc {
 // out[r] = X_r . Y_r for r < m (X_r = X + r ldx, Y_r = Y + r ldy); scratch >= dot_scratch_size(m)
 void vec_dots(const double* X, int ldx, const double* Y, int ldy, int n, int m, double* scratch, double* out,
               hipStream_t s);
+constexpr int kRedSets = 128;  // dot products the context's reduction scratch holds at once
 int dot_scratch_size(int m);
+// out[r mx + j] = X_j . Y_r for j < mx, r < my (rows ldx and ldy apart), in two launches; the same sums in
+// the same order as vec_dots; scratch of dot_scratch_size(mx my).
+void vec_gram(const double* X, int ldx, const double* Y, int ldy, int n, int mx, int my, double* scratch,
+              double* out, hipStream_t s);
 // out = gamma - tau g / sqrt(gg[0])
 void vec_trial(const double* gamma, const double* g, const double* gg, double tau, double* out, int n,
                hipStream_t s);

@@ -83,6 +83,31 @@ void vec_dots(const double* X, int ldx, const double* Y, int ldy, int n, int m, 
 
 int dot_scratch_size(int m) { return kRedBlocks * m; }
 
+// Partial sums of the Gram entries X_j . Y_r, blockIdx.y = r mx + j (the blocks and tree of k_dot_partial).
+__global__ void k_gram_partial(const double* __restrict__ X, int ldx, const double* __restrict__ Y, int ldy, int n,
+                               int mx, double* __restrict__ partial) {
+  __shared__ double sm[256];
+  const int j = blockIdx.y % mx, r = blockIdx.y / mx;
+  const double* x = X + (size_t)j * ldx;
+  const double* y = Y + (size_t)r * ldy;
+  double v = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) v += x[i] * y[i];
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = sm[0];
+}
+
+void vec_gram(const double* X, int ldx, const double* Y, int ldy, int n, int mx, int my, double* scratch,
+              double* out, hipStream_t s) {
+  const int nb = std::min(kRedBlocks, std::max(1, cdiv(n, 256)));
+  hipLaunchKernelGGL(k_gram_partial, dim3(nb, mx * my), dim3(256), 0, s, X, ldx, Y, ldy, n, mx, scratch);
+  hipLaunchKernelGGL(k_dot_final, dim3(mx * my), dim3(256), 0, s, scratch, nb, out);
+}
+
 // ---------------------------------------------------------------------------
 // dense products (the coarsest level's saddle operator)
 // ---------------------------------------------------------------------------

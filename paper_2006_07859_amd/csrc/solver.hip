@@ -515,12 +515,19 @@ rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma,
       cons_scale_rows(k.rows, w, k.nrm, nV, nb, k.rowsW, s);
       rows2 = k.rowsW;
     }
-    for (int r = 0; r < nb; ++r)
-      vec_dots(k.rows, 3 * nV, rows2 + (size_t)r * 3 * nV, 0, 3 * nV, nb, c->red, k.dots + r * nb, s);
+    // the Gram products in one pair of launches each while the scratch holds nb^2 partial sets
+    const bool gram = nb * nb <= kRedSets;
+    if (gram) vec_gram(k.rows, 3 * nV, rows2, 3 * nV, 3 * nV, nb, nb, c->red, k.dots, s);
+    else
+      for (int r = 0; r < nb; ++r)
+        vec_dots(k.rows, 3 * nV, rows2 + (size_t)r * 3 * nV, 0, 3 * nV, nb, c->red, k.dots + r * nb, s);
     if (np > 0) {
       cons_path_apply(k.geo, cv.edges, k.path_edge, np, rows2, nV, nb, k.Kpb, s);
       tri_solve(path_sys(k), k.Kpb, np, k.Z, np, nb, k.sp_g, k.sp_U, s);
-      for (int r = 0; r < nb; ++r) vec_dots(k.Kpb, np, k.Z + (size_t)r * np, 0, np, nb, c->red, k.small + r * nb, s);
+      if (gram) vec_gram(k.Kpb, np, k.Z, np, np, nb, nb, c->red, k.small, s);
+      else
+        for (int r = 0; r < nb; ++r)
+          vec_dots(k.Kpb, np, k.Z + (size_t)r * np, 0, np, nb, c->red, k.small + r * nb, s);
     }
     // a border row that vanishes on the free vertices (a cut edge with both ends pinned) is zero
     // in S: a unit diagonal gives it a zero multiplier
