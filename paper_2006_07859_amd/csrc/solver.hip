@@ -1159,8 +1159,8 @@ static rc_status mg_prepare(rc_ctx* c, const double* gamma) {
   for (int pass = 0; npw > 0; ++pass) {
     for (int q = 0; q < npw; ++q) {
       if (done[q]) continue;
-      const int todo = pass == 0 ? (c->mg[pw_levels[q]].lmax > 0.0 ? 3 : 8) : 1;
-      for (int k = 0; k < todo; ++k) RC_TRY(power_step(q, its[q]++));
+      const int count = pass == 0 ? (c->mg[pw_levels[q]].lmax > 0.0 ? 3 : 8) : 1;
+      for (int k = 0; k < count; ++k) RC_TRY(power_step(q, its[q]++));
     }
     RC_TRY(fetch(c, c->scal + kPwSlot0, h.data(), 2 * npw));
     bool all = true;
