@@ -44,8 +44,11 @@ def make(g, e, a, b, dtype, mask, tang, pins=None):
 
 
 @pytest.mark.parametrize("mask,tedges,with_pins", [(BARY, [5, 150], False), (BARY | EDGE, [5, 150], False),
-                                                   (BARY | EDGE, [5, 150, 299], False), (EDGE, [5, 150], True)])
+                                                   (BARY | EDGE, [5, 150, 299], False), (EDGE, [5, 150], True),
+                                                   (BARY | EDGE, list(range(3, 300, 15)), False)])
 def test_tangent_values_and_projector(lib, mask, tedges, with_pins):
+    """(The last case has 20 tangents: 3 + 40 + 1 border rows, more than the device inverts, so the
+    border Schur complement is inverted on the host.)"""
     from paper_2006_07859_amd import RC_F64
 
     n = 300
