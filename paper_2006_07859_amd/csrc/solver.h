@@ -247,8 +247,9 @@ void cons_free(Cons& k);
 // Failures of the constraint set-up latched in rc_ctx::setup_flags.
 constexpr unsigned kSetupGram = 1u;   // the path block's tridiagonal factorisation broke down
 constexpr unsigned kSetupSchur = 2u;  // the border Schur complement is singular
-// Enqueues the factors of C C^T (or C W C^T) without waiting for the device: a failed factorisation is
-// latched in c->setup_flags and reported by setup_check.
+// Enqueues the factors of C C^T (or C W C^T) without waiting for the device (except for a border of
+// more than kSchurDevMax rows, whose Schur complement is inverted on the host): a failed factorisation
+// is latched in c->setup_flags and reported by setup_check.
 rc_status cons_prepare(rc_ctx* c, const Curve& cv, Cons& k, const double* gamma, const double* w = nullptr);
 // Waits for the stream, reports (and clears) the constraint set-up's latched failures.
 rc_status setup_check(rc_ctx* c);
